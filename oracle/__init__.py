@@ -1,0 +1,388 @@
+"""Oracle: plain FP64 CPU reference of the tangent-point hot path.
+
+TEST INFRASTRUCTURE ONLY -- imported by the tests, by ``__graft_entry__.smoke()`` and by
+the CPU-baseline leg of ``bench.py``; never by the library.  It shares no code with the
+HIP path.  The pair sums live in ``tp_oracle.c`` (plain loops, double precision); the
+sparse and small dense linear algebra lives here on numpy/scipy.
+
+Every function cites the passage of "Repulsive Surfaces" (Yu et al. 2021) it writes out.
+Readings of points the paper leaves open are listed in the docstrings.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+from scipy.sparse.csgraph import connected_components
+
+from . import build as _build
+
+_lib = None
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = _build.build(force=False)
+        L = ctypes.CDLL(path)
+        i64, d = ctypes.c_int64, ctypes.c_double
+        L.tpo_faces.argtypes = [_dp, _ip, i64, _dp, _dp, _dp]
+        L.tpo_energy_faces_rows.argtypes = [_dp, _dp, _dp, i64, d, d, i64, i64, _dp]
+        L.tpo_energy_faces.argtypes = [_dp, _dp, _dp, i64, d, d]
+        L.tpo_energy_faces.restype = d
+        L.tpo_energy.argtypes = [_dp, i64, _ip, i64, d, d]
+        L.tpo_energy.restype = d
+        L.tpo_gradient_rows.argtypes = [_dp, i64, _ip, i64, d, d, i64, i64, _dp, _dp]
+        L.tpo_face_to_vertex.argtypes = [_dp, i64, _ip, i64, _dp, _dp]
+        L.tpo_gradient.argtypes = [_dp, i64, _ip, i64, d, d, _dp]
+        L.tpo_gradient.restype = d
+        L.tpo_fractional_rows.argtypes = [_dp, i64, _ip, i64, d, _dp, ctypes.c_int, i64, i64, _dp]
+        L.tpo_fractional_apply.argtypes = [_dp, i64, _ip, i64, d, _dp, ctypes.c_int, _dp]
+        L.tpo_fractional_apply.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+def _prep(V, F):
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    F = np.ascontiguousarray(F, dtype=np.int32)
+    assert V.ndim == 2 and V.shape[1] == 3 and F.ndim == 2 and F.shape[1] == 3
+    return V, F
+
+
+# ----------------------------------------------------------------------------------
+# Exponents.  The paper fixes alpha = p, beta = 2p with p = 6 (Sec. 2.1) and derives
+# s = 2 - n/p for surfaces (n = 2, Sec. 2.3); the preconditioner applies L^sigma with
+# sigma = 2 - s (Sec. 5.2).  For independent (alpha, beta) we read s = (beta - 2)/alpha,
+# which equals 2 - 2/p when beta = 2 alpha (an extrapolation, flagged in the design notes).
+DEFAULT_ALPHA = 6.0
+DEFAULT_BETA = 12.0
+
+
+def sobolev_s(alpha: float = DEFAULT_ALPHA, beta: float = DEFAULT_BETA) -> float:
+    return (beta - 2.0) / alpha
+
+
+def preconditioner_sigma(alpha: float = DEFAULT_ALPHA, beta: float = DEFAULT_BETA) -> float:
+    return 2.0 - sobolev_s(alpha, beta)
+
+
+# ----------------------------------------------------------------------------------
+# Pair sums (C).
+
+def faces(V, F):
+    """Barycenters X (nF x 3), unit normals N (nF x 3), areas a (nF) (Sec. 3.1)."""
+    V, F = _prep(V, F)
+    nF = F.shape[0]
+    X, N, A = np.empty((nF, 3)), np.empty((nF, 3)), np.empty(nF)
+    lib().tpo_faces(_d(V), _i(F), nF, _d(X), _d(N), _d(A))
+    return X, N, A
+
+
+def energy_faces(X, N, A, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA) -> float:
+    """E = sum_S sum_{T != S} K(S,T) a_S a_T on given face quantities (eq. DiscreteEnergy)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    N = np.ascontiguousarray(N, dtype=np.float64)
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    return float(lib().tpo_energy_faces(_d(X), _d(N), _d(A), A.shape[0], alpha, beta))
+
+
+def energy(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA) -> float:
+    """Discrete tangent-point energy (eq. DiscreteEnergy with eq. DiscreteTangentPointKernel)."""
+    V, F = _prep(V, F)
+    return float(lib().tpo_energy(_d(V), V.shape[0], _i(F), F.shape[0], alpha, beta))
+
+
+def gradient(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
+    """(E, dE) with dE (nV x 3) the exact differential by the chain rule (Sec. 3.1)."""
+    V, F = _prep(V, F)
+    dE = np.empty_like(V)
+    E = lib().tpo_gradient(_d(V), V.shape[0], _i(F), F.shape[0], alpha, beta, _d(dE))
+    return float(E), dE
+
+
+def gradient_rows(V, F, s0, s1, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
+    """Per-face partial derivatives (dE/dX_S, dE/dN_S, dE/da_S) and energy rows for
+    faces S in [s0, s1): the pair loop of ``gradient`` over a band of rows."""
+    V, F = _prep(V, F)
+    n = s1 - s0
+    g = np.empty((n, 7))
+    Erow = np.empty(n)
+    lib().tpo_gradient_rows(_d(V), V.shape[0], _i(F), F.shape[0], alpha, beta, s0, s1, _d(g), _d(Erow))
+    return g, Erow
+
+
+def fractional_apply(V, F, u, sigma=None, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
+    """L^sigma u for u of shape (nV,) or (nV, k), k <= 64 (eq. DiscreteLaplacianQuartic)."""
+    V, F = _prep(V, F)
+    if sigma is None:
+        sigma = preconditioner_sigma(alpha, beta)
+    u = np.asarray(u, dtype=np.float64)
+    vec = u.ndim == 1
+    U = np.ascontiguousarray(u.reshape(u.shape[0], -1))
+    k = U.shape[1]
+    Lu = np.empty_like(U)
+    rc = lib().tpo_fractional_apply(_d(V), V.shape[0], _i(F), F.shape[0], sigma, _d(U), k, _d(Lu))
+    if rc != 0:
+        raise ValueError("k must be in [1, 64]")
+    return Lu[:, 0] if vec else Lu
+
+
+def fractional_rows(V, F, u, s0, s1, sigma):
+    V, F = _prep(V, F)
+    U = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(V.shape[0], -1))
+    k = U.shape[1]
+    w = np.empty((s1 - s0, k))
+    lib().tpo_fractional_rows(_d(V), V.shape[0], _i(F), F.shape[0], sigma, _d(U), k, s0, s1, _d(w))
+    return w
+
+
+# ----------------------------------------------------------------------------------
+# Dense fractional operator by Algorithm 1 (tiny meshes only).
+
+def dense_fractional_matrix(V, F, sigma):
+    """|V| x |V| matrix L^sigma assembled pair by pair as in Algorithm 1 (Sec. 2.4).
+
+    'All distinct pairs of faces' is read as all ordered pairs S != T, which is the sum
+    of eq. DiscreteLaplacianQuartic; phi_i(S) = 1/3 for the corners of S, 0 otherwise."""
+    V, F = _prep(V, F)
+    X, _, A = faces(V, F)
+    nV, nF = V.shape[0], F.shape[0]
+    L = np.zeros((nV, nV))
+    for S in range(nF):
+        for T in range(nF):
+            if S == T:
+                continue
+            verts = sorted(set(F[S].tolist()) | set(F[T].tolist()))
+            phiS = {v: (1.0 / 3.0 if v in F[S] else 0.0) for v in verts}
+            phiT = {v: (1.0 / 3.0 if v in F[T] else 0.0) for v in verts}
+            h = np.linalg.norm(X[S] - X[T]) ** (-(2.0 * sigma + 2.0)) * A[S] * A[T]
+            for i in verts:
+                for j in verts:
+                    L[i, j] += (phiS[i] - phiT[i]) * (phiS[j] - phiT[j]) * h
+    return L
+
+
+# ----------------------------------------------------------------------------------
+# Cotan Laplacian, components and Poisson solves (Sec. 5.2).
+
+def cotan_laplacian(V, F):
+    """Weak (stiffness) cotan Laplacian C with C_ij = -1/2 (cot alpha_ij + cot beta_ij) for
+    each edge ij and C_ii = -sum_j C_ij.  The paper names only 'the sparse cotan-weighted
+    Laplace-Beltrami operator' (Sec. 5.2); this is the textbook form."""
+    V, F = _prep(V, F)
+    nV = V.shape[0]
+    rows, cols, vals = [], [], []
+    for c in range(3):
+        i, j, k = F[:, c], F[:, (c + 1) % 3], F[:, (c + 2) % 3]
+        u = V[j] - V[i]
+        w = V[k] - V[i]
+        cot = np.einsum("ij,ij->i", u, w) / np.linalg.norm(np.cross(u, w), axis=1)
+        h = 0.5 * cot  # weight of the edge (j,k) opposite corner i
+        rows += [j, k, j, k]
+        cols += [k, j, j, k]
+        vals += [-h, -h, h, h]
+    C = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(nV, nV)).tocsr()
+    C.sum_duplicates()
+    return C
+
+
+def components(F, nV):
+    """Connected-component label of every vertex (Sec. 7.1 treats each component apart)."""
+    F = np.asarray(F)
+    r = np.concatenate([F[:, 0], F[:, 1], F[:, 2]])
+    c = np.concatenate([F[:, 1], F[:, 2], F[:, 0]])
+    G = sp.coo_matrix((np.ones(r.size), (r, c)), shape=(nV, nV))
+    n, labels = connected_components(G, directed=False)
+    return n, labels
+
+
+def project_mean_zero(x, labels, ncomp=None):
+    """Subtract the unweighted per-component mean of every column (reading of the fixed
+    barycenter constraint, Sec. 7.1.1, folded into the Laplacians as in Sec. 7.2)."""
+    x = np.array(x, dtype=np.float64, copy=True)
+    X2 = x.reshape(x.shape[0], -1)
+    if ncomp is None:
+        ncomp = int(labels.max()) + 1
+    for c in range(ncomp):
+        m = labels == c
+        X2[m] -= X2[m].mean(axis=0)
+    return x
+
+
+def poisson_solve(C, b, labels):
+    """Exact solution x of C x = P b with P x = x (per-component mean zero), by a sparse
+    direct solve of C bordered with one indicator row per component."""
+    b = np.asarray(b, dtype=np.float64)
+    B2 = b.reshape(b.shape[0], -1)
+    nV = C.shape[0]
+    ncomp = int(labels.max()) + 1
+    Bm = sp.coo_matrix((np.ones(nV), (labels, np.arange(nV))), shape=(ncomp, nV))
+    M = sp.bmat([[C, Bm.T], [Bm, None]], format="csc")
+    Pb = project_mean_zero(B2, labels, ncomp)
+    rhs = np.vstack([Pb, np.zeros((ncomp, B2.shape[1]))])
+    sol = spla.splu(M).solve(rhs)
+    return sol[:nV].reshape(b.shape)
+
+
+# ----------------------------------------------------------------------------------
+# Constraints (Sec. 7.1.3, 7.1.4).
+
+def total_area(V, F) -> float:
+    _, _, A = faces(V, F)
+    return float(A.sum())
+
+
+def total_volume(V, F) -> float:
+    """Signed volume (1/6) sum_{(ijk)} f_i . (f_j x f_k)."""
+    V, F = _prep(V, F)
+    return float(np.einsum("ij,ij->i", V[F[:, 0]], np.cross(V[F[:, 1]], V[F[:, 2]])).sum() / 6.0)
+
+
+def area_gradient(V, F):
+    """d(sum_S a_S)/df: for face (i,j,k), d a_S / d f_i = (1/2) N_S x (f_k - f_j), and
+    cyclically for j and k."""
+    V, F = _prep(V, F)
+    _, N, _ = faces(V, F)
+    g = np.zeros_like(V)
+    for c in range(3):
+        i, j, k = F[:, c], F[:, (c + 1) % 3], F[:, (c + 2) % 3]
+        np.add.at(g, i, 0.5 * np.cross(N, V[k] - V[j]))
+    return g
+
+
+def volume_gradient(V, F):
+    """d Vol/df: for face (i,j,k), d/d f_i [f_i . (f_j x f_k)]/6 = (f_j x f_k)/6, cyclically."""
+    V, F = _prep(V, F)
+    g = np.zeros_like(V)
+    for c in range(3):
+        i, j, k = F[:, c], F[:, (c + 1) % 3], F[:, (c + 2) % 3]
+        np.add.at(g, i, np.cross(V[j], V[k]) / 6.0)
+    return g
+
+
+# ----------------------------------------------------------------------------------
+# Preconditioner (Sec. 5.2) and one projected descent step (Sec. 3, 5.3, 5.4).
+
+def precond_apply(V, F, b, sigma=None, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, C=None, labels=None):
+    """A~^{-1} b = C^+ P L^sigma C^+ P b, columnwise (Sec. 5.2).
+
+    Readings: both Laplace-Beltrami factors are the weak cotan matrix C with no mass
+    matrix; C^+ P b is the per-component mean-zero solution of C x = P b."""
+    V, F = _prep(V, F)
+    if sigma is None:
+        sigma = preconditioner_sigma(alpha, beta)
+    if C is None:
+        C = cotan_laplacian(V, F)
+    if labels is None:
+        _, labels = components(F, V.shape[0])
+    y = poisson_solve(C, b, labels)
+    z = fractional_apply(V, F, y, sigma)
+    return poisson_solve(C, z, labels)
+
+
+@dataclass
+class StepResult:
+    V: np.ndarray          # new vertex positions
+    E: float               # energy at the start of the step
+    grad_norm: float
+    tau: float
+    backtracks: int
+    direction: np.ndarray  # projected descent direction x (nV x 3)
+    phi_before: np.ndarray  # Phi(f)
+    phi_after: np.ndarray   # Phi after the corrective step
+    phi_trial: np.ndarray = field(default_factory=lambda: np.zeros(0))  # Phi(f + tau x)
+    schur: np.ndarray = field(default_factory=lambda: np.zeros((0, 0)))
+
+
+ARMIJO_C = 1e-4
+ARMIJO_SHRINK = 0.5
+ARMIJO_MAX_BACKTRACKS = 30
+
+
+def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=None,
+                 line_search=True, constrain_area=True, constrain_volume=True,
+                 area_target=None, volume_target=None):
+    """One constrained descent step with A~^{-1} in place of A_3^{-1}.
+
+    1. g = dE (Sec. 3.1).  2. J = rows of the active constraints: total area (Sec. 7.1.3)
+    and total volume (Sec. 7.1.4).  3. Y = A~^{-1} J^T, y_g = A~^{-1} g; Schur matrix
+    S = J Y (the paper's -(M/A), eq. SchurComplementMA); direction
+    x = -(y_g - Y S^{-1} J y_g), which solves eq. SaddleProblem with A_3^{-1} -> A~^{-1}
+    (eq. SchurProjectedExpression, with the sign of the descent direction).
+    4. Armijo backtracking from tau0 (constants c = 1e-4, shrink 1/2, at most 30 halvings;
+    the paper names the rule but not the constants).  tau0 defaults to the step whose
+    largest vertex move is half the mean edge length.  With line_search=False, tau = tau0.
+    5. Corrective step h = -Y S^{-1} Phi(f + tau x) (Sec. 5.4.1), added to f + tau x."""
+    V, F = _prep(V, F)
+    nV = V.shape[0]
+    if sigma is None:
+        sigma = preconditioner_sigma(alpha, beta)
+    C = cotan_laplacian(V, F)
+    _, labels = components(F, nV)
+    E0, g = gradient(V, F, alpha, beta)
+    A0 = total_area(V, F) if area_target is None else area_target
+    V0 = total_volume(V, F) if volume_target is None else volume_target
+    rows, targets, fns = [], [], []
+    if constrain_area:
+        rows.append(area_gradient(V, F)); targets.append(A0); fns.append(total_area)
+    if constrain_volume:
+        rows.append(volume_gradient(V, F)); targets.append(V0); fns.append(total_volume)
+    R = np.concatenate([g] + rows, axis=1)           # nV x 3(1 + k)
+    Y = precond_apply(V, F, R, sigma, C=C, labels=labels)
+    yg = Y[:, 0:3]
+    k = len(rows)
+    YJ = [Y[:, 3 + 3 * m: 6 + 3 * m] for m in range(k)]
+    S = np.array([[np.vdot(rows[a], YJ[b]) for b in range(k)] for a in range(k)]).reshape(k, k)
+    if k:
+        rhs = np.array([np.vdot(rows[a], yg) for a in range(k)])
+        mu = np.linalg.solve(S, rhs)
+        x = -(yg - sum(mu[m] * YJ[m] for m in range(k)))
+    else:
+        x = -yg
+    phi_before = np.array([fns[m](V, F) - targets[m] for m in range(k)])
+    slope = float(np.vdot(g, x))
+    if tau is None:
+        from_edges = 0.5 * _mean_edge_length(V, F)
+        tau0 = from_edges / np.abs(np.linalg.norm(x, axis=1)).max()
+    else:
+        tau0 = float(tau)
+    t = tau0
+    bt = 0
+    if line_search:
+        while energy(V + t * x, F, alpha, beta) > E0 + ARMIJO_C * t * slope and bt < ARMIJO_MAX_BACKTRACKS:
+            t *= ARMIJO_SHRINK
+            bt += 1
+    Vt = V + t * x
+    if k:
+        phi = np.array([fns[m](Vt, F) - targets[m] for m in range(k)])
+        lam = np.linalg.solve(S, phi)
+        h = -sum(lam[m] * YJ[m] for m in range(k))
+        Vn = Vt + h
+        phi_after = np.array([fns[m](Vn, F) - targets[m] for m in range(k)])
+    else:
+        Vn = Vt
+        phi = phi_after = phi_before
+    return StepResult(V=Vn, E=E0, grad_norm=float(np.linalg.norm(g)), tau=t, backtracks=bt,
+                      direction=x, phi_before=phi_before, phi_after=phi_after, phi_trial=phi, schur=S)
+
+
+def _mean_edge_length(V, F) -> float:
+    e = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]])
+    e = np.unique(np.sort(e, axis=1), axis=0)
+    return float(np.linalg.norm(V[e[:, 0]] - V[e[:, 1]], axis=1).mean())

@@ -1,0 +1,295 @@
+/*
+ * tp_oracle.c -- plain FP64 CPU reference for the tangent-point hot path of
+ * "Repulsive Surfaces" (Yu, Brakensiek, Schumacher, Crane 2021).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library.  It shares no code with the HIP path.
+ *
+ * Everything here is the paper's definition written out with plain loops in double
+ * precision: no blocking, no fusion, no reordering of the sums beyond splitting the
+ * outer sum over faces S into rows, which are reduced in increasing S order, so the
+ * result does not depend on the number of OpenMP threads.
+ *
+ * Conventions: V is nV x 3 row-major double, F is nF x 3 int32 with 0-based vertex
+ * indices.  A face S = (i, j, k) has edges e1 = f_j - f_i, e2 = f_k - f_i.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define EXPORT __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------------- */
+/* Face quantities (Sec. 3.1, eq. DiscreteTangentPointKernel and the text after
+ * eq. DiscreteEnergy): barycenter X_S, area a_S, unit normal N_S.  The normal
+ * enters only through the projector N N^T, so its sign is irrelevant (Sec. 2.1). */
+static void face_quantities(const double* V, const int32_t* F, int64_t s,
+                            double X[3], double N[3], double* a, double c[3])
+{
+    const double* fi = V + 3 * (int64_t)F[3 * s + 0];
+    const double* fj = V + 3 * (int64_t)F[3 * s + 1];
+    const double* fk = V + 3 * (int64_t)F[3 * s + 2];
+    double e1[3], e2[3];
+    for (int d = 0; d < 3; ++d) {
+        X[d] = (fi[d] + fj[d] + fk[d]) / 3.0;
+        e1[d] = fj[d] - fi[d];
+        e2[d] = fk[d] - fi[d];
+    }
+    c[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    c[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    c[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    double cn = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    *a = 0.5 * cn;
+    for (int d = 0; d < 3; ++d) N[d] = c[d] / cn;
+}
+
+EXPORT void tpo_faces(const double* V, const int32_t* F, int64_t nF,
+                      double* X, double* N, double* A)
+{
+    for (int64_t s = 0; s < nF; ++s) {
+        double c[3];
+        face_quantities(V, F, s, X + 3 * s, N + 3 * s, A + s, c);
+    }
+}
+
+static void all_faces(const double* V, const int32_t* F, int64_t nF,
+                      double* X, double* N, double* A, double* C)
+{
+    for (int64_t s = 0; s < nF; ++s)
+        face_quantities(V, F, s, X + 3 * s, N + 3 * s, A + s, C + 3 * s);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Discrete tangent-point kernel (eq. DiscreteTangentPointKernel) with independent
+ * exponents: K(S,T) = |P_S d|^alpha / |d|^beta, d = X_S - X_T, P_S = N_S N_S^T.
+ * Since |N_S| = 1, |P_S d| = |N_S . d|.  The paper's choice is alpha = p, beta = 2p. */
+static double tp_kernel(const double XS[3], const double NS[3], const double XT[3],
+                        double alpha, double beta)
+{
+    double d[3] = {XS[0] - XT[0], XS[1] - XT[1], XS[2] - XT[2]};
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double q = NS[0] * d[0] + NS[1] * d[1] + NS[2] * d[2];
+    return pow(fabs(q), alpha) * pow(r2, -0.5 * beta);
+}
+
+/* Partial derivatives of K(S,T) with respect to d = X_S - X_T and to N_S:
+ *   dK/dd = alpha |q|^(alpha-1) sgn(q) |d|^-beta N_S - beta K |d|^-2 d,
+ *   dK/dN = alpha |q|^(alpha-1) sgn(q) |d|^-beta d,       q = N_S . d.        */
+static double tp_kernel_grad(const double XS[3], const double NS[3], const double XT[3],
+                             double alpha, double beta, double dKdd[3], double dKdN[3])
+{
+    double d[3] = {XS[0] - XT[0], XS[1] - XT[1], XS[2] - XT[2]};
+    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    double q = NS[0] * d[0] + NS[1] * d[1] + NS[2] * d[2];
+    double rb = pow(r2, -0.5 * beta);
+    double K = pow(fabs(q), alpha) * rb;
+    double sq = (q > 0.0) ? 1.0 : ((q < 0.0) ? -1.0 : 0.0);
+    double c1 = alpha * pow(fabs(q), alpha - 1.0) * sq * rb;
+    double c2 = beta * K / r2;
+    for (int m = 0; m < 3; ++m) {
+        dKdd[m] = c1 * NS[m] - c2 * d[m];
+        dKdN[m] = c1 * d[m];
+    }
+    return K;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Energy (eq. DiscreteEnergy): E = sum_S sum_{T != S} K(S,T) a_S a_T.
+ * The diagonal S = T is excluded: K(S,S) is 0/0, and the kernel matrix of
+ * Sec. 5.1 carries the factor (1 - delta_ST).
+ * E depends on the mesh only through the face quantities (X, N, a), so the sum is
+ * written on those: Erow[s - s0] = sum_{T != S} K(S,T) a_S a_T for S in [s0, s1),
+ * X and N are nF x 3 row-major.                                                   */
+EXPORT void tpo_energy_faces_rows(const double* X, const double* N, const double* A, int64_t nF,
+                                  double alpha, double beta, int64_t s0, int64_t s1, double* Erow)
+{
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t S = s0; S < s1; ++S) {
+        double row = 0.0;
+        for (int64_t T = 0; T < nF; ++T) {
+            if (T == S) continue;
+            row += tp_kernel(X + 3 * S, N + 3 * S, X + 3 * T, alpha, beta) * A[S] * A[T];
+        }
+        Erow[S - s0] = row;
+    }
+}
+
+EXPORT double tpo_energy_faces(const double* X, const double* N, const double* A, int64_t nF,
+                               double alpha, double beta)
+{
+    double* Erow = malloc(sizeof(double) * nF);
+    tpo_energy_faces_rows(X, N, A, nF, alpha, beta, 0, nF, Erow);
+    double E = 0.0;
+    for (int64_t S = 0; S < nF; ++S) E += Erow[S];
+    free(Erow);
+    return E;
+}
+
+EXPORT double tpo_energy(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                         double alpha, double beta)
+{
+    (void)nV;
+    double* X = malloc(sizeof(double) * 3 * nF);
+    double* N = malloc(sizeof(double) * 3 * nF);
+    double* A = malloc(sizeof(double) * nF);
+    double* C = malloc(sizeof(double) * 3 * nF);
+    all_faces(V, F, nF, X, N, A, C);
+    double E = tpo_energy_faces(X, N, A, nF, alpha, beta);
+    free(X); free(N); free(A); free(C);
+    return E;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Differential of E by the chain rule (text after eq. DiscreteEnergy).
+ *
+ * E depends on f only through the face quantities X, N, a.  For a face S, the terms
+ * that involve S are the pairs (S,T) (S first: depends on X_S, N_S, a_S) and (T,S)
+ * (S second: depends on X_S, a_S).  Summing their partial derivatives:
+ *
+ *   dE/dX_S = sum_T [ a_S a_T dK(S,T)/dd  -  a_T a_S dK(T,S)/dd' ]   (d' = X_T - X_S)
+ *   dE/dN_S = sum_T   a_S a_T dK(S,T)/dN_S
+ *   dE/da_S = sum_T [ K(S,T) a_T + K(T,S) a_T ]
+ *
+ * gface[7 s + 0..2] = dE/dX_S, [3..5] = dE/dN_S, [6] = dE/da_S for S in [s0, s1);
+ * Erow[s - s0] as in tpo_energy_faces_rows.                                            */
+EXPORT void tpo_gradient_rows(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                              double alpha, double beta, int64_t s0, int64_t s1,
+                              double* gface, double* Erow)
+{
+    (void)nV;
+    double* X = malloc(sizeof(double) * 3 * nF);
+    double* N = malloc(sizeof(double) * 3 * nF);
+    double* A = malloc(sizeof(double) * nF);
+    double* C = malloc(sizeof(double) * 3 * nF);
+    all_faces(V, F, nF, X, N, A, C);
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t S = s0; S < s1; ++S) {
+        double gX[3] = {0, 0, 0}, gN[3] = {0, 0, 0}, ga = 0.0, row = 0.0;
+        for (int64_t T = 0; T < nF; ++T) {
+            if (T == S) continue;
+            double dKdd[3], dKdN[3], dKdd_r[3], dKdN_r[3];
+            double K = tp_kernel_grad(X + 3 * S, N + 3 * S, X + 3 * T, alpha, beta, dKdd, dKdN);
+            double Kr = tp_kernel_grad(X + 3 * T, N + 3 * T, X + 3 * S, alpha, beta, dKdd_r, dKdN_r);
+            double w = A[S] * A[T];
+            for (int m = 0; m < 3; ++m) {
+                gX[m] += w * dKdd[m] - w * dKdd_r[m];
+                gN[m] += w * dKdN[m];
+            }
+            ga += K * A[T] + Kr * A[T];
+            row += K * w;
+        }
+        double* g = gface + 7 * (S - s0);
+        for (int m = 0; m < 3; ++m) { g[m] = gX[m]; g[3 + m] = gN[m]; }
+        g[6] = ga;
+        if (Erow) Erow[S - s0] = row;
+    }
+    free(X); free(N); free(A); free(C);
+}
+
+/* Chain rule from face quantities to vertex positions.
+ *   X_S = (f_i + f_j + f_k)/3                      -> each corner gets dE/dX_S / 3
+ *   c = e1 x e2, a_S = |c|/2, N_S = c/|c|          -> g_c = (I - N N^T) dE/dN_S / |c| + dE/da_S N_S / 2
+ *   dc = (df_j - df_i) x e2 + e1 x (df_k - df_i)   -> df_j: e2 x g_c,  df_k: g_c x e1,  df_i: -(both)
+ * Faces are visited in increasing order, so the vertex sums are deterministic. */
+EXPORT void tpo_face_to_vertex(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                               const double* gface, double* dE)
+{
+    memset(dE, 0, sizeof(double) * 3 * nV);
+    for (int64_t S = 0; S < nF; ++S) {
+        double X[3], N[3], a, c[3];
+        face_quantities(V, F, S, X, N, &a, c);
+        const double* g = gface + 7 * S;
+        const double* fi = V + 3 * (int64_t)F[3 * S + 0];
+        const double* fj = V + 3 * (int64_t)F[3 * S + 1];
+        const double* fk = V + 3 * (int64_t)F[3 * S + 2];
+        double e1[3], e2[3];
+        for (int m = 0; m < 3; ++m) { e1[m] = fj[m] - fi[m]; e2[m] = fk[m] - fi[m]; }
+        double cn = 2.0 * a;
+        double ndg = N[0] * g[3] + N[1] * g[4] + N[2] * g[5];
+        double gc[3];
+        for (int m = 0; m < 3; ++m) gc[m] = (g[3 + m] - N[m] * ndg) / cn + 0.5 * g[6] * N[m];
+        double dj[3] = {e2[1] * gc[2] - e2[2] * gc[1], e2[2] * gc[0] - e2[0] * gc[2], e2[0] * gc[1] - e2[1] * gc[0]};
+        double dk[3] = {gc[1] * e1[2] - gc[2] * e1[1], gc[2] * e1[0] - gc[0] * e1[2], gc[0] * e1[1] - gc[1] * e1[0]};
+        int64_t vi = F[3 * S + 0], vj = F[3 * S + 1], vk = F[3 * S + 2];
+        for (int m = 0; m < 3; ++m) {
+            double gx = g[m] / 3.0;
+            dE[3 * vi + m] += gx - dj[m] - dk[m];
+            dE[3 * vj + m] += gx + dj[m];
+            dE[3 * vk + m] += gx + dk[m];
+        }
+    }
+}
+
+EXPORT double tpo_gradient(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                           double alpha, double beta, double* dE)
+{
+    double* gface = malloc(sizeof(double) * 7 * nF);
+    double* Erow = malloc(sizeof(double) * nF);
+    tpo_gradient_rows(V, nV, F, nF, alpha, beta, 0, nF, gface, Erow);
+    tpo_face_to_vertex(V, nV, F, nF, gface, dE);
+    double E = 0.0;
+    for (int64_t S = 0; S < nF; ++S) E += Erow[S];
+    free(gface); free(Erow);
+    return E;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Fractional operator applied to k columns (eq. DiscreteLaplacianQuartic):
+ *
+ *   (L u)_i = sum_{S != T} (phi_i(S) - phi_i(T)) (ubar(S) - ubar(T)) |X_S - X_T|^-(2 sigma + 2) a_S a_T
+ *
+ * where ubar(S) = sum_j phi_j(S) u_j is the average of u over the corners of S
+ * (phi_j(S) = 1/3 for the corners of S, 0 otherwise).  The part carrying phi_i(T)
+ * equals the part carrying phi_i(S) after renaming S <-> T (the rest of the summand is
+ * antisymmetric times symmetric), so
+ *
+ *   (L u)_i = 2 sum_S phi_i(S) w(S),   w(S) = sum_{T != S} (ubar(S) - ubar(T)) |X_S - X_T|^-(2 sigma + 2) a_S a_T.
+ *
+ * u and Lu are nV x k row-major.  wrow[(s - s0) k + c] = w(S) for S in [s0, s1). */
+EXPORT void tpo_fractional_rows(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                                double sigma, const double* u, int k,
+                                int64_t s0, int64_t s1, double* wrow)
+{
+    (void)nV;
+    double* X = malloc(sizeof(double) * 3 * nF);
+    double* N = malloc(sizeof(double) * 3 * nF);
+    double* A = malloc(sizeof(double) * nF);
+    double* C = malloc(sizeof(double) * 3 * nF);
+    double* ub = malloc(sizeof(double) * nF * k);
+    all_faces(V, F, nF, X, N, A, C);
+    for (int64_t S = 0; S < nF; ++S)
+        for (int c = 0; c < k; ++c)
+            ub[S * k + c] = (u[(int64_t)F[3 * S] * k + c] + u[(int64_t)F[3 * S + 1] * k + c] +
+                             u[(int64_t)F[3 * S + 2] * k + c]) / 3.0;
+    double expo = -(2.0 * sigma + 2.0) * 0.5;  /* |d|^-(2 sigma + 2) = (|d|^2)^expo */
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int64_t S = s0; S < s1; ++S) {
+        double acc[64];
+        for (int c = 0; c < k; ++c) acc[c] = 0.0;
+        for (int64_t T = 0; T < nF; ++T) {
+            if (T == S) continue;
+            double d0 = X[3 * S] - X[3 * T], d1 = X[3 * S + 1] - X[3 * T + 1], d2 = X[3 * S + 2] - X[3 * T + 2];
+            double h = pow(d0 * d0 + d1 * d1 + d2 * d2, expo) * A[S] * A[T];
+            for (int c = 0; c < k; ++c) acc[c] += (ub[S * k + c] - ub[T * k + c]) * h;
+        }
+        for (int c = 0; c < k; ++c) wrow[(S - s0) * k + c] = acc[c];
+    }
+    free(X); free(N); free(A); free(C); free(ub);
+}
+
+EXPORT int tpo_fractional_apply(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                                double sigma, const double* u, int k, double* Lu)
+{
+    if (k < 1 || k > 64) return 1;
+    double* w = malloc(sizeof(double) * nF * k);
+    tpo_fractional_rows(V, nV, F, nF, sigma, u, k, 0, nF, w);
+    memset(Lu, 0, sizeof(double) * nV * k);
+    for (int64_t S = 0; S < nF; ++S)
+        for (int corner = 0; corner < 3; ++corner) {
+            int64_t i = F[3 * S + corner];
+            for (int c = 0; c < k; ++c) Lu[i * k + c] += 2.0 * (w[S * k + c] / 3.0);
+        }
+    free(w);
+    return 0;
+}
