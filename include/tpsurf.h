@@ -1,0 +1,213 @@
+/*
+ * tpsurf.h -- C-ABI of the tangent-point hot path of "Repulsive Surfaces"
+ * (Yu, Brakensiek, Schumacher, Crane, ACM TOG 2021) on AMD MI355X (gfx950).
+ *
+ * What the library computes, on a closed triangle mesh M = (V, F) with embedding f:
+ *   - the discrete tangent-point energy E (Sec. 3.1, eq. DiscreteEnergy with the kernel
+ *     of eq. DiscreteTangentPointKernel), with independent exponents (alpha, beta),
+ *     the paper's choice being (p, 2p) with p = 6 (Sec. 2.1);
+ *   - its differential dE with respect to the vertex positions (Sec. 3.1, chain rule);
+ *   - the forward application of the fractional operator L^sigma (Sec. 2.4, eq.
+ *     DiscreteLaplacianQuartic) in the factored kernel-matrix form of Sec. 5.1.1 / App. A;
+ *   - the preconditioner A~^{-1} = C^{-1} L^sigma C^{-1} of Sec. 5.2, with both Poisson
+ *     solves done by FP64 conjugate gradients on the cotan stiffness matrix C;
+ *   - one projected descent step with total-area and total-volume constraints (Sec. 3,
+ *     eq. SaddleProblem via the Schur complement of Sec. 5.3, Armijo line search, and the
+ *     corrective projection of Sec. 5.4.1), A~^{-1} standing in for A_3^{-1}.
+ *
+ * Conventions shared by every entry point
+ *   - V: vertex positions, nV x 3, row-major double.  F: faces, nF x 3, row-major int32,
+ *     0-based vertex indices, consistently oriented (orientation only fixes the sign of
+ *     the volume; the energy uses the normal projector, which ignores it).
+ *   - Unless stated otherwise, array arguments are DEVICE pointers on the current HIP
+ *     device (for example torch tensors' data_ptr()), scalars out-parameters are HOST
+ *     pointers.  The caller owns every buffer; the library keeps no pointer to caller
+ *     memory after a call returns.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Every call
+ *     is ordered on that stream and returns after its work has completed.
+ *   - Errors are returned as tp_status; no exception crosses the ABI.  tp_last_error()
+ *     gives a message for the calling thread.  On error the outputs are undefined, except
+ *     for TP_E_NOT_CONVERGED, where outputs and reports are written.
+ *   - Results are deterministic: no floating-point atomics, fixed reduction orders.
+ */
+#ifndef TPSURF_H
+#define TPSURF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TPSURF_VERSION 1
+
+#if defined(__GNUC__) || defined(__clang__)
+#define TP_API __attribute__((visibility("default")))
+#else
+#define TP_API
+#endif
+
+typedef enum {
+    TP_OK = 0,
+    TP_E_INVALID_ARGUMENT = 1,       /* bad size, pointer, exponent or option           */
+    TP_E_DEGENERATE_FACE = 2,        /* a face has zero area: its normal is undefined  */
+    TP_E_BAD_INDEX = 3,              /* a face refers to a vertex outside [0, nV)      */
+    TP_E_NONFINITE = 4,              /* non-finite input or result (e.g. two faces with
+                                        coincident barycenters make the kernel infinite) */
+    TP_E_NOT_CONVERGED = 5,          /* CG reached cg_maxiter before cg_rtol            */
+    TP_E_OUT_OF_MEMORY = 6,
+    TP_E_SINGULAR_CONSTRAINTS = 7,   /* the Schur matrix J A~^{-1} J^T is singular      */
+    TP_E_DEVICE = 8                  /* a HIP runtime error                             */
+} tp_status;
+
+/* Arithmetic of the all-pairs sums.  Accumulation is always FP64 per face. */
+typedef enum {
+    TP_PREC_FP32_HILO = 0,  /* FP32 pair terms; barycenter differences from hi+lo FP32
+                               splits of the FP64 barycenters (default)                   */
+    TP_PREC_FP32 = 1,       /* FP32 pair terms from FP32-rounded barycenters              */
+    TP_PREC_FP64 = 2        /* FP64 pair terms                                            */
+} tp_precision;
+
+typedef struct {
+    double alpha;        /* numerator exponent, default 6 (p, Sec. 2.1); must be > 1    */
+    double beta;         /* denominator exponent, default 12 (2p); must be > 0          */
+    double sigma;        /* order parameter of L^sigma; < 0 selects 2 - s with
+                            s = (beta - 2)/alpha (= 2 - 2/p when beta = 2 alpha,
+                            Sec. 2.3 and Sec. 5.2); default -1 -> 1/3 at p = 6           */
+    int    precision;    /* tp_precision, default TP_PREC_FP32_HILO                      */
+    double cg_rtol;      /* CG stops when ||b - C x|| <= cg_rtol ||b||, default 1e-10   */
+    int    cg_maxiter;   /* default 20000                                               */
+} tp_params;
+
+/* Fill *p with the defaults above. */
+TP_API tp_status tp_params_default(tp_params* p);
+
+/* ---------------------------------------------------------------- stateless calls */
+
+/* E = sum_S sum_{T != S} K(S,T) a_S a_T (eq. DiscreteEnergy; the diagonal is excluded).
+ * E_out: host pointer to one double. */
+TP_API tp_status tp_energy(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                    const tp_params* params, double* E_out, void* stream);
+
+/* E and dE (Sec. 3.1).  dE_out: device, nV x 3 row-major double. */
+TP_API tp_status tp_gradient(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                      const tp_params* params, double* E_out, double* dE_out, void* stream);
+
+/* E on face quantities directly: X, N nF x 3 row-major double (N unit), a nF double,
+ * all device pointers.  E depends on the mesh only through these (Sec. 4.1 writes the
+ * kernel as K_p(X_S, P_S; X_T)). */
+TP_API tp_status tp_energy_faces(const double* X, const double* N, const double* a, int64_t nF,
+                          const tp_params* params, double* E_out, void* stream);
+
+/* Lu = L^sigma u for k columns (eq. DiscreteLaplacianQuartic, factored as
+ * 2 U^T [diag(diag(a)^-1 H a) - H] U of Sec. 5.1.1, H_ST = (1 - delta_ST)|X_S - X_T|^-(2 sigma + 2)).
+ * u, Lu_out: device, nV x k row-major double, 1 <= k <= 64. */
+TP_API tp_status tp_fractional_apply(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                              const tp_params* params, const double* u, int k,
+                              double* Lu_out, void* stream);
+
+/* Report of one preconditioner application (two CG solves). */
+typedef struct {
+    int    cg_iters[2];      /* largest iteration count over the columns, per solve      */
+    double cg_relres[2];     /* largest final ||r||/||b|| over the columns, per solve     */
+    double t_ms[4];          /* CG 1, fractional apply, CG 2, total (device time)        */
+} tp_solve_report;
+
+/* x = A~^{-1} b = C^+ P L^sigma C^+ P b columnwise (Sec. 5.2): P subtracts the unweighted
+ * per-connected-component mean, C^+ P y is the per-component mean-zero solution of
+ * C x = P y by FP64 CG.  b, x_out: device, nV x k row-major, 1 <= k <= 64.
+ * report may be NULL. */
+TP_API tp_status tp_precond_apply(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                           const tp_params* params, const double* b, int k, double* x_out,
+                           tp_solve_report* report, void* stream);
+
+/* ----------------------------------------------------- resident problem (stateful) */
+
+/* A problem keeps the topology (vertex-face incidence, cotan sparsity, components), the
+ * current vertex positions and all work buffers on the device, so repeated calls do no
+ * allocation or host-side preprocessing.  A problem is used by one thread at a time. */
+typedef struct tp_problem tp_problem;
+
+/* Copies V and F (device pointers) into a new problem on the current device. */
+TP_API tp_status tp_problem_create(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                            const tp_params* params, void* stream, tp_problem** out);
+TP_API void      tp_problem_destroy(tp_problem* prob);
+
+/* Replace / read the current vertex positions (device, nV x 3). */
+TP_API tp_status tp_problem_set_vertices(tp_problem* prob, const double* V);
+TP_API tp_status tp_problem_get_vertices(tp_problem* prob, double* V_out);
+
+/* Same operations as the stateless calls, on the problem's current vertices. */
+TP_API tp_status tp_problem_energy(tp_problem* prob, double* E_out);
+TP_API tp_status tp_problem_gradient(tp_problem* prob, double* E_out, double* dE_out);
+TP_API tp_status tp_problem_fractional_apply(tp_problem* prob, const double* u, int k, double* Lu_out);
+TP_API tp_status tp_problem_precond_apply(tp_problem* prob, const double* b, int k, double* x_out,
+                                   tp_solve_report* report);
+
+/* Options of one descent step. */
+typedef struct {
+    double tau0;             /* initial step; <= 0 selects the step whose largest vertex
+                                move is half the mean edge length of the initial mesh     */
+    int    line_search;      /* 1: Armijo backtracking from tau0; 0: take tau0           */
+    double armijo_c;         /* sufficient-decrease constant, default 1e-4               */
+    double shrink;           /* backtracking factor, default 0.5                         */
+    int    max_backtracks;   /* default 30                                               */
+    int    constrain_area;   /* total-area constraint row (Sec. 7.1.3), default 1        */
+    int    constrain_volume; /* total-volume constraint row (Sec. 7.1.4), default 1      */
+    double area_target;      /* NaN selects the area of the mesh at tp_problem_create    */
+    double volume_target;    /* NaN selects the volume at tp_problem_create              */
+} tp_step_opts;
+
+TP_API tp_status tp_step_opts_default(tp_step_opts* o);
+
+typedef struct {
+    double E;                /* energy at the start of the step                          */
+    double E_new;            /* energy after the step (after the corrective projection)  */
+    double grad_norm;        /* ||dE||_2                                                 */
+    double slope;            /* dE . x (negative for a descent direction)                */
+    double tau;              /* accepted step size                                       */
+    int    backtracks;
+    int    n_constraints;
+    int    cg_iters[2];
+    double cg_relres[2];
+    double phi_before[2];    /* constraint values Phi(f) (area, volume; unused rows 0)   */
+    double phi_trial[2];     /* Phi(f + tau x)                                           */
+    double phi_after[2];     /* Phi after the corrective step                            */
+    double t_ms[8];          /* gradient, constraints, preconditioner, Schur, line search,
+                                projection, total, (unused)                               */
+} tp_step_report;
+
+/* One projected, preconditioned descent step (Sec. 3 steps 1-5 with Sec. 5.3-5.4):
+ * g = dE; J = active constraint rows; Y = A~^{-1} J^T, y_g = A~^{-1} g (one 3(1+k)-column
+ * preconditioner application); S = J Y; x = -(y_g - Y S^{-1} J y_g); Armijo on E(f + tau x);
+ * f <- f + tau x - Y S^{-1} Phi(f + tau x).  The problem's vertices are updated.
+ * direction_out: optional device nV x 3 buffer receiving x (may be NULL).
+ * report may be NULL. */
+TP_API tp_status tp_precond_step(tp_problem* prob, const tp_step_opts* opts, tp_step_report* report,
+                          double* direction_out);
+
+/* ------------------------------------------------------------------- diagnostics */
+
+/* Message describing the last error of the calling thread ("" if none). */
+TP_API const char* tp_last_error(void);
+
+/* Kernel timing for roofline reports.  When enabled, every all-pairs kernel launch is
+ * bracketed by HIP events recorded on the stream it runs on; the elapsed device time,
+ * the number of ordered face pairs it covered and the launch count are accumulated per
+ * kind: 0 = energy, 1 = energy + differential, 2 = fractional apply.  Process-global. */
+typedef struct {
+    double  ms_total;      /* summed device time of the launches                        */
+    double  pairs_total;   /* summed ordered pairs S != T evaluated (columns not counted) */
+    double  cols_total;    /* summed pairs x columns (fractional apply only)             */
+    int64_t launches;
+} tp_kernel_stats;
+
+TP_API tp_status tp_profile_enable(int on);
+TP_API tp_status tp_profile_reset(void);
+TP_API tp_status tp_profile_get(int kind, tp_kernel_stats* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TPSURF_H */

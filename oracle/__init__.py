@@ -45,6 +45,10 @@ def lib():
         L.tpo_fractional_rows.argtypes = [_dp, i64, _ip, i64, d, _dp, ctypes.c_int, i64, i64, _dp]
         L.tpo_fractional_apply.argtypes = [_dp, i64, _ip, i64, d, _dp, ctypes.c_int, _dp]
         L.tpo_fractional_apply.restype = ctypes.c_int
+        _lp = ctypes.POINTER(ctypes.c_int64)
+        L.tpo_gradient_rowlist.argtypes = [_dp, i64, _ip, i64, d, d, _lp, i64, _dp, _dp]
+        L.tpo_fractional_rowlist.argtypes = [_dp, i64, _ip, i64, d, _dp, ctypes.c_int, _lp, i64, _dp]
+        L.tpo_fractional_gather.argtypes = [_ip, i64, i64, _dp, ctypes.c_int, _dp]
         _lib = L
     return _lib
 
@@ -124,6 +128,44 @@ def gradient_rows(V, F, s0, s1, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
     Erow = np.empty(n)
     lib().tpo_gradient_rows(_d(V), V.shape[0], _i(F), F.shape[0], alpha, beta, s0, s1, _d(g), _d(Erow))
     return g, Erow
+
+
+def _incident_faces(F, verts):
+    F = np.asarray(F)
+    mask = np.isin(F, np.asarray(verts)).any(axis=1)
+    return np.nonzero(mask)[0].astype(np.int64)
+
+
+def gradient_at_vertices(V, F, verts, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
+    """Exact dE at the listed vertices only: the pair sums are taken for the faces incident
+    to them (all T), then chained to vertices; O(|faces| nF) instead of O(nF^2)."""
+    V, F = _prep(V, F)
+    rows = _incident_faces(F, verts)
+    g = np.zeros((F.shape[0], 7))
+    gr = np.empty((rows.size, 7))
+    lib().tpo_gradient_rowlist(_d(V), V.shape[0], _i(F), F.shape[0], alpha, beta,
+                               rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), rows.size,
+                               _d(gr), None)
+    g[rows] = gr
+    dE = np.empty_like(V)
+    lib().tpo_face_to_vertex(_d(V), V.shape[0], _i(F), F.shape[0], _d(g), _d(dE))
+    return dE[np.asarray(verts)]
+
+
+def fractional_at_vertices(V, F, u, verts, sigma):
+    """Exact (L^sigma u) at the listed vertices only (rows of the incident faces)."""
+    V, F = _prep(V, F)
+    U = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(V.shape[0], -1))
+    k = U.shape[1]
+    rows = _incident_faces(F, verts)
+    w = np.zeros((F.shape[0], k))
+    wr = np.empty((rows.size, k))
+    lib().tpo_fractional_rowlist(_d(V), V.shape[0], _i(F), F.shape[0], sigma, _d(U), k,
+                                 rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), rows.size, _d(wr))
+    w[rows] = wr
+    Lu = np.empty((V.shape[0], k))
+    lib().tpo_fractional_gather(_i(F), F.shape[0], V.shape[0], _d(w), k, _d(Lu))
+    return Lu[np.asarray(verts)]
 
 
 def fractional_apply(V, F, u, sigma=None, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):

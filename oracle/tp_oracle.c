@@ -153,6 +153,28 @@ EXPORT double tpo_energy(const double* V, int64_t nV, const int32_t* F, int64_t 
  *
  * gface[7 s + 0..2] = dE/dX_S, [3..5] = dE/dN_S, [6] = dE/da_S for S in [s0, s1);
  * Erow[s - s0] as in tpo_energy_faces_rows.                                            */
+static void gradient_row(const double* X, const double* N, const double* A, int64_t nF,
+                         double alpha, double beta, int64_t S, double g[7], double* Erow)
+{
+    double gX[3] = {0, 0, 0}, gN[3] = {0, 0, 0}, ga = 0.0, row = 0.0;
+    for (int64_t T = 0; T < nF; ++T) {
+        if (T == S) continue;
+        double dKdd[3], dKdN[3], dKdd_r[3], dKdN_r[3];
+        double K = tp_kernel_grad(X + 3 * S, N + 3 * S, X + 3 * T, alpha, beta, dKdd, dKdN);
+        double Kr = tp_kernel_grad(X + 3 * T, N + 3 * T, X + 3 * S, alpha, beta, dKdd_r, dKdN_r);
+        double w = A[S] * A[T];
+        for (int m = 0; m < 3; ++m) {
+            gX[m] += w * dKdd[m] - w * dKdd_r[m];
+            gN[m] += w * dKdN[m];
+        }
+        ga += K * A[T] + Kr * A[T];
+        row += K * w;
+    }
+    for (int m = 0; m < 3; ++m) { g[m] = gX[m]; g[3 + m] = gN[m]; }
+    g[6] = ga;
+    if (Erow) *Erow = row;
+}
+
 EXPORT void tpo_gradient_rows(const double* V, int64_t nV, const int32_t* F, int64_t nF,
                               double alpha, double beta, int64_t s0, int64_t s1,
                               double* gface, double* Erow)
@@ -164,26 +186,25 @@ EXPORT void tpo_gradient_rows(const double* V, int64_t nV, const int32_t* F, int
     double* C = malloc(sizeof(double) * 3 * nF);
     all_faces(V, F, nF, X, N, A, C);
 #pragma omp parallel for schedule(dynamic, 8)
-    for (int64_t S = s0; S < s1; ++S) {
-        double gX[3] = {0, 0, 0}, gN[3] = {0, 0, 0}, ga = 0.0, row = 0.0;
-        for (int64_t T = 0; T < nF; ++T) {
-            if (T == S) continue;
-            double dKdd[3], dKdN[3], dKdd_r[3], dKdN_r[3];
-            double K = tp_kernel_grad(X + 3 * S, N + 3 * S, X + 3 * T, alpha, beta, dKdd, dKdN);
-            double Kr = tp_kernel_grad(X + 3 * T, N + 3 * T, X + 3 * S, alpha, beta, dKdd_r, dKdN_r);
-            double w = A[S] * A[T];
-            for (int m = 0; m < 3; ++m) {
-                gX[m] += w * dKdd[m] - w * dKdd_r[m];
-                gN[m] += w * dKdN[m];
-            }
-            ga += K * A[T] + Kr * A[T];
-            row += K * w;
-        }
-        double* g = gface + 7 * (S - s0);
-        for (int m = 0; m < 3; ++m) { g[m] = gX[m]; g[3 + m] = gN[m]; }
-        g[6] = ga;
-        if (Erow) Erow[S - s0] = row;
-    }
+    for (int64_t S = s0; S < s1; ++S)
+        gradient_row(X, N, A, nF, alpha, beta, S, gface + 7 * (S - s0), Erow ? Erow + (S - s0) : NULL);
+    free(X); free(N); free(A); free(C);
+}
+
+/* Same per-face sums for an explicit list of faces rows[0..nrows). */
+EXPORT void tpo_gradient_rowlist(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                                 double alpha, double beta, const int64_t* rows, int64_t nrows,
+                                 double* gface, double* Erow)
+{
+    (void)nV;
+    double* X = malloc(sizeof(double) * 3 * nF);
+    double* N = malloc(sizeof(double) * 3 * nF);
+    double* A = malloc(sizeof(double) * nF);
+    double* C = malloc(sizeof(double) * 3 * nF);
+    all_faces(V, F, nF, X, N, A, C);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nrows; ++q)
+        gradient_row(X, N, A, nF, alpha, beta, rows[q], gface + 7 * q, Erow ? Erow + q : NULL);
     free(X); free(N); free(A); free(C);
 }
 
@@ -247,35 +268,71 @@ EXPORT double tpo_gradient(const double* V, int64_t nV, const int32_t* F, int64_
  *   (L u)_i = 2 sum_S phi_i(S) w(S),   w(S) = sum_{T != S} (ubar(S) - ubar(T)) |X_S - X_T|^-(2 sigma + 2) a_S a_T.
  *
  * u and Lu are nV x k row-major.  wrow[(s - s0) k + c] = w(S) for S in [s0, s1). */
+static void fractional_prepare(const double* V, const int32_t* F, int64_t nF, const double* u, int k,
+                               double** X, double** A, double** ub)
+{
+    double* N = malloc(sizeof(double) * 3 * nF);
+    double* C = malloc(sizeof(double) * 3 * nF);
+    *X = malloc(sizeof(double) * 3 * nF);
+    *A = malloc(sizeof(double) * nF);
+    *ub = malloc(sizeof(double) * nF * k);
+    all_faces(V, F, nF, *X, N, *A, C);
+    for (int64_t S = 0; S < nF; ++S)
+        for (int c = 0; c < k; ++c)
+            (*ub)[S * k + c] = (u[(int64_t)F[3 * S] * k + c] + u[(int64_t)F[3 * S + 1] * k + c] +
+                                u[(int64_t)F[3 * S + 2] * k + c]) / 3.0;
+    free(N); free(C);
+}
+
+static void fractional_row(const double* X, const double* A, const double* ub, int64_t nF, int k,
+                           double sigma, int64_t S, double* out)
+{
+    double acc[64];
+    double expo = -(2.0 * sigma + 2.0) * 0.5;  /* |d|^-(2 sigma + 2) = (|d|^2)^expo */
+    for (int c = 0; c < k; ++c) acc[c] = 0.0;
+    for (int64_t T = 0; T < nF; ++T) {
+        if (T == S) continue;
+        double d0 = X[3 * S] - X[3 * T], d1 = X[3 * S + 1] - X[3 * T + 1], d2 = X[3 * S + 2] - X[3 * T + 2];
+        double h = pow(d0 * d0 + d1 * d1 + d2 * d2, expo) * A[S] * A[T];
+        for (int c = 0; c < k; ++c) acc[c] += (ub[S * k + c] - ub[T * k + c]) * h;
+    }
+    for (int c = 0; c < k; ++c) out[c] = acc[c];
+}
+
 EXPORT void tpo_fractional_rows(const double* V, int64_t nV, const int32_t* F, int64_t nF,
                                 double sigma, const double* u, int k,
                                 int64_t s0, int64_t s1, double* wrow)
 {
     (void)nV;
-    double* X = malloc(sizeof(double) * 3 * nF);
-    double* N = malloc(sizeof(double) * 3 * nF);
-    double* A = malloc(sizeof(double) * nF);
-    double* C = malloc(sizeof(double) * 3 * nF);
-    double* ub = malloc(sizeof(double) * nF * k);
-    all_faces(V, F, nF, X, N, A, C);
-    for (int64_t S = 0; S < nF; ++S)
-        for (int c = 0; c < k; ++c)
-            ub[S * k + c] = (u[(int64_t)F[3 * S] * k + c] + u[(int64_t)F[3 * S + 1] * k + c] +
-                             u[(int64_t)F[3 * S + 2] * k + c]) / 3.0;
-    double expo = -(2.0 * sigma + 2.0) * 0.5;  /* |d|^-(2 sigma + 2) = (|d|^2)^expo */
+    double *X, *A, *ub;
+    fractional_prepare(V, F, nF, u, k, &X, &A, &ub);
 #pragma omp parallel for schedule(dynamic, 8)
-    for (int64_t S = s0; S < s1; ++S) {
-        double acc[64];
-        for (int c = 0; c < k; ++c) acc[c] = 0.0;
-        for (int64_t T = 0; T < nF; ++T) {
-            if (T == S) continue;
-            double d0 = X[3 * S] - X[3 * T], d1 = X[3 * S + 1] - X[3 * T + 1], d2 = X[3 * S + 2] - X[3 * T + 2];
-            double h = pow(d0 * d0 + d1 * d1 + d2 * d2, expo) * A[S] * A[T];
-            for (int c = 0; c < k; ++c) acc[c] += (ub[S * k + c] - ub[T * k + c]) * h;
+    for (int64_t S = s0; S < s1; ++S) fractional_row(X, A, ub, nF, k, sigma, S, wrow + (S - s0) * k);
+    free(X); free(A); free(ub);
+}
+
+EXPORT void tpo_fractional_rowlist(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                                   double sigma, const double* u, int k, const int64_t* rows,
+                                   int64_t nrows, double* wrow)
+{
+    (void)nV;
+    double *X, *A, *ub;
+    fractional_prepare(V, F, nF, u, k, &X, &A, &ub);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nrows; ++q) fractional_row(X, A, ub, nF, k, sigma, rows[q], wrow + q * k);
+    free(X); free(A); free(ub);
+}
+
+/* (L u)_i = 2 sum_S phi_i(S) w(S) with phi_i(S) = 1/3 on the corners of S. */
+EXPORT void tpo_fractional_gather(const int32_t* F, int64_t nF, int64_t nV, const double* w, int k,
+                                  double* Lu)
+{
+    memset(Lu, 0, sizeof(double) * nV * k);
+    for (int64_t S = 0; S < nF; ++S)
+        for (int corner = 0; corner < 3; ++corner) {
+            int64_t i = F[3 * S + corner];
+            for (int c = 0; c < k; ++c) Lu[i * k + c] += 2.0 * (w[S * k + c] / 3.0);
         }
-        for (int c = 0; c < k; ++c) wrow[(S - s0) * k + c] = acc[c];
-    }
-    free(X); free(N); free(A); free(C); free(ub);
 }
 
 EXPORT int tpo_fractional_apply(const double* V, int64_t nV, const int32_t* F, int64_t nF,
@@ -284,12 +341,7 @@ EXPORT int tpo_fractional_apply(const double* V, int64_t nV, const int32_t* F, i
     if (k < 1 || k > 64) return 1;
     double* w = malloc(sizeof(double) * nF * k);
     tpo_fractional_rows(V, nV, F, nF, sigma, u, k, 0, nF, w);
-    memset(Lu, 0, sizeof(double) * nV * k);
-    for (int64_t S = 0; S < nF; ++S)
-        for (int corner = 0; corner < 3; ++corner) {
-            int64_t i = F[3 * S + corner];
-            for (int c = 0; c < k; ++c) Lu[i * k + c] += 2.0 * (w[S * k + c] / 3.0);
-        }
+    tpo_fractional_gather(F, nF, nV, w, k, Lu);
     free(w);
     return 0;
 }

@@ -1,0 +1,1015 @@
+// C-ABI of libtpsurf: validation, resident problem state and the host orchestration of
+// the hot path (energy, differential, fractional apply, preconditioner, descent step).
+#include "tp_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <numeric>
+#include <vector>
+
+namespace tp {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+void set_error(const std::string& msg) { g_err = msg; }
+const char* get_error() { return g_err.c_str(); }
+
+static tp_status fail(tp_status st, const std::string& msg)
+{
+    set_error(msg);
+    return st;
+}
+
+// ------------------------------------------------------------------ device info
+
+const DeviceInfo& device_info()
+{
+    static std::mutex mu;
+    static DeviceInfo info[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    DeviceInfo& d = info[dev];
+    if (d.device < 0) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            d.num_cu = prop.multiProcessorCount;
+            d.max_threads_per_cu = prop.maxThreadsPerMultiProcessor;
+        } else {
+            d.num_cu = 256;
+            d.max_threads_per_cu = 2048;
+        }
+        d.device = dev;
+    }
+    return d;
+}
+
+// ------------------------------------------------------------------ kernel timing
+
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    tp_kernel_stats st[3];
+};
+static Profiler g_prof;
+
+struct PairTimer {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool on = false;
+    int kind = 0;
+    double pairs = 0, cols = 0;
+    hipStream_t s = nullptr;
+    PairTimer(int kind_, double pairs_, double cols_, hipStream_t s_) : kind(kind_), pairs(pairs_), cols(cols_), s(s_)
+    {
+        {
+            std::lock_guard<std::mutex> lk(g_prof.mu);
+            on = g_prof.on;
+        }
+        if (on) {
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) on = false;
+            else (void)hipEventRecord(a, s);
+        }
+    }
+    void stop()
+    {
+        if (!on) return;
+        (void)hipEventRecord(b, s);
+    }
+    ~PairTimer()
+    {
+        if (on) {
+            float ms = 0.f;
+            if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess) {
+                std::lock_guard<std::mutex> lk(g_prof.mu);
+                g_prof.st[kind].ms_total += ms;
+                g_prof.st[kind].pairs_total += pairs;
+                g_prof.st[kind].cols_total += cols;
+                g_prof.st[kind].launches += 1;
+            }
+        }
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// ------------------------------------------------------------------ device buffers
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // Grow to at least cnt elements (contents are not preserved).
+    tp_status ensure(size_t cnt, hipStream_t s)
+    {
+        if (cnt <= n && p) return TP_OK;
+        if (p) {
+            if (hipStreamSynchronize(s) != hipSuccess) return fail(TP_E_DEVICE, "stream sync failed");
+            release();
+        }
+        size_t want = std::max<size_t>(cnt, 1);
+        if (hipMalloc((void**)&p, want * sizeof(T)) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return fail(TP_E_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(want * sizeof(T)) + " bytes failed");
+        }
+        n = want;
+        return TP_OK;
+    }
+};
+
+}  // namespace tp
+
+using namespace tp;
+
+// ------------------------------------------------------------------ problem state
+
+struct tp_problem {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    tp_params prm;
+    double sigma = 1.0 / 3.0;
+    int64_t nV = 0, nF = 0, cap = 0;
+
+    DevBuf<double> V;
+    DevBuf<int32_t> F;
+    FaceData fd;
+    DevBuf<float4> fx, fl, fn;
+    DevBuf<double4> dx, dn;
+    DevBuf<int> flags;
+    bool geom_valid = false;     // fd describes V
+    bool cotan_valid = false;    // lap_val describes V
+
+    // topology (built on first use)
+    bool have_vf = false, have_lap = false;
+    DevBuf<int32_t> vf_off, vf_idx, tmp_i, tmp_j;
+    DevBuf<int32_t> lap_off, lap_col, comp;
+    DevBuf<double> lap_val, inv_count;
+    int64_t nnz = 0;
+    int ncomp = 0;
+
+    double area0 = 0, vol0 = 0, mean_edge = 0;
+
+    // work
+    DevBuf<double> part, gface, zbuf, scal, red, vol6, edge;
+    DevBuf<char> ub;
+    DevBuf<double> cg_r, cg_q, cg_p, cg_red, cg_relres;
+    DevBuf<unsigned> cg_bar;
+    DevBuf<int> cg_iters;
+    DevBuf<double> R, Y, W1, W2, gbuf, dir, Vt, Vsave;
+};
+
+namespace {
+
+// Per-face edge-length sums (for the mean edge length of the initial mesh).
+__global__ void k_face_edges(const double* __restrict__ V, const int32_t* __restrict__ F, int64_t nF,
+                             double* __restrict__ out)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nF) return;
+    double s = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double* a = V + 3 * (int64_t)F[3 * f + c];
+        const double* b = V + 3 * (int64_t)F[3 * f + (c + 1) % 3];
+        const double d0 = a[0] - b[0], d1 = a[1] - b[1], d2 = a[2] - b[2];
+        s += sqrt(d0 * d0 + d1 * d1 + d2 * d2);
+    }
+    out[f] = s;
+}
+
+tp_status validate_params(const tp_params* in, tp_params& out, double& sigma)
+{
+    tp_params_default(&out);
+    if (in) out = *in;
+    if (!(out.alpha > 1.0) || !std::isfinite(out.alpha))
+        return fail(TP_E_INVALID_ARGUMENT, "alpha must be a finite number > 1");
+    if (!(out.beta > 0.0) || !std::isfinite(out.beta))
+        return fail(TP_E_INVALID_ARGUMENT, "beta must be a finite number > 0");
+    if (out.precision < 0 || out.precision > 2) return fail(TP_E_INVALID_ARGUMENT, "unknown precision");
+    if (!(out.cg_rtol > 0.0)) return fail(TP_E_INVALID_ARGUMENT, "cg_rtol must be > 0");
+    if (out.cg_maxiter < 1) return fail(TP_E_INVALID_ARGUMENT, "cg_maxiter must be >= 1");
+    sigma = out.sigma;
+    if (sigma < 0.0) {
+        const double s = (out.beta - 2.0) / out.alpha;   // s = 2 - 2/p when beta = 2 alpha
+        sigma = 2.0 - s;
+    }
+    if (!(sigma > 0.0 && sigma < 1.0))
+        return fail(TP_E_INVALID_ARGUMENT, "sigma must lie in (0, 1) (fractional order 2 sigma in (0, 2))");
+    return TP_OK;
+}
+
+tp_status check_flags(tp_problem* P)
+{
+    int h[kNumFlags] = {0, 0, 0, 0};
+    TP_HIP(hipMemcpyAsync(h, P->flags.p, sizeof(h), hipMemcpyDeviceToHost, P->stream));
+    TP_HIP(hipStreamSynchronize(P->stream));
+    if (h[0] | h[1] | h[2] | h[3]) TP_HIP(hipMemsetAsync(P->flags.p, 0, sizeof(h), P->stream));
+    if (h[kFlagBadIndex]) return fail(TP_E_BAD_INDEX, "a face refers to a vertex index outside [0, nV)");
+    if (h[kFlagNonFinite]) return fail(TP_E_NONFINITE, "non-finite vertex coordinates or face quantities");
+    if (h[kFlagDegenerate]) return fail(TP_E_DEGENERATE_FACE, "a face has zero area (its normal is undefined)");
+    if (h[kFlagCgAbort]) return fail(TP_E_DEVICE, "CG workgroup barrier timed out");
+    return TP_OK;
+}
+
+// Read one device double (synchronous).
+tp_status read_scalars(tp_problem* P, const double* dev, double* host, int n)
+{
+    TP_HIP(hipMemcpyAsync(host, dev, sizeof(double) * n, hipMemcpyDeviceToHost, P->stream));
+    TP_HIP(hipStreamSynchronize(P->stream));
+    return TP_OK;
+}
+
+tp_status alloc_faces(tp_problem* P)
+{
+    P->cap = face_capacity(P->nF, 4);
+    TP_TRY(P->fx.ensure(P->cap, P->stream));
+    TP_TRY(P->fl.ensure(P->cap, P->stream));
+    TP_TRY(P->fn.ensure(P->cap, P->stream));
+    TP_TRY(P->dx.ensure(P->cap, P->stream));
+    TP_TRY(P->dn.ensure(P->cap, P->stream));
+    P->fd.nF = P->nF;
+    P->fd.cap = P->cap;
+    P->fd.fx = P->fx.p;
+    P->fd.fl = P->fl.p;
+    P->fd.fn = P->fn.p;
+    P->fd.dx = P->dx.p;
+    P->fd.dn = P->dn.p;
+    TP_TRY(P->flags.ensure(kNumFlags, P->stream));
+    TP_HIP(hipMemsetAsync(P->flags.p, 0, sizeof(int) * kNumFlags, P->stream));
+    TP_TRY(P->scal.ensure(256, P->stream));
+    TP_TRY(P->red.ensure(reduce_scratch_doubles(16), P->stream));
+    return TP_OK;
+}
+
+// Face quantities at vertices Vsrc (defaults to the problem's vertices).
+tp_status geometry(tp_problem* P, const double* Vsrc = nullptr)
+{
+    const double* src = Vsrc ? Vsrc : P->V.p;
+    TP_HIP(launch_face_geom(src, P->nV, P->F.p, P->nF, P->fd, P->flags.p, P->stream));
+    TP_TRY(check_flags(P));
+    P->geom_valid = (Vsrc == nullptr);
+    return TP_OK;
+}
+
+tp_status ensure_geometry(tp_problem* P)
+{
+    if (!P->geom_valid) TP_TRY(geometry(P));
+    return TP_OK;
+}
+
+tp_status ensure_vf(tp_problem* P)
+{
+    if (P->have_vf) return TP_OK;
+    hipStream_t s = P->stream;
+    TP_TRY(P->vf_off.ensure(P->nV + 1, s));
+    TP_TRY(P->vf_idx.ensure(3 * P->nF, s));
+    TP_TRY(P->tmp_i.ensure(P->nV + 1, s));
+    TP_HIP(hipMemsetAsync(P->tmp_i.p, 0, sizeof(int32_t) * (P->nV + 1), s));
+    TP_HIP(launch_vf_count(P->F.p, P->nF, P->nV, P->tmp_i.p, s));
+    TP_HIP(launch_scan(P->tmp_i.p, P->nV, P->vf_off.p, s));
+    TP_HIP(hipMemsetAsync(P->tmp_i.p, 0, sizeof(int32_t) * (P->nV + 1), s));
+    TP_HIP(launch_vf_fill(P->F.p, P->nF, P->nV, P->vf_off.p, P->tmp_i.p, P->vf_idx.p, s));
+    TP_HIP(launch_sort_rows(P->vf_off.p, P->nV, P->vf_idx.p, s));
+    P->have_vf = true;
+    return TP_OK;
+}
+
+// Cotan sparsity pattern and connected components (host union-find on a copy of F).
+tp_status ensure_lap(tp_problem* P)
+{
+    if (P->have_lap) return TP_OK;
+    TP_TRY(ensure_vf(P));
+    hipStream_t s = P->stream;
+    TP_TRY(P->tmp_j.ensure(6 * P->nF + 1, s));
+    TP_TRY(P->lap_off.ensure(P->nV + 1, s));
+    TP_HIP(launch_lap_pattern_count(P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->tmp_j.p, P->tmp_i.p, s));
+    TP_HIP(launch_scan(P->tmp_i.p, P->nV, P->lap_off.p, s));
+    int32_t nnz = 0;
+    TP_HIP(hipMemcpyAsync(&nnz, P->lap_off.p + P->nV, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    P->nnz = nnz;
+    TP_TRY(P->lap_col.ensure(std::max<int64_t>(nnz, 1), s));
+    TP_TRY(P->lap_val.ensure(std::max<int64_t>(nnz, 1), s));
+    TP_HIP(launch_lap_pattern_fill(P->nV, P->vf_off.p, P->tmp_j.p, P->lap_off.p, P->lap_col.p, s));
+
+    // connected components over the face graph
+    std::vector<int32_t> hF(3 * P->nF);
+    TP_HIP(hipMemcpyAsync(hF.data(), P->F.p, sizeof(int32_t) * 3 * P->nF, hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    std::vector<int32_t> parent(P->nV);
+    std::iota(parent.begin(), parent.end(), 0);
+    auto find = [&](int32_t a) {
+        while (parent[a] != a) {
+            parent[a] = parent[parent[a]];
+            a = parent[a];
+        }
+        return a;
+    };
+    for (int64_t f = 0; f < P->nF; ++f)
+        for (int c = 1; c < 3; ++c) {
+            int32_t a = find(hF[3 * f]), b = find(hF[3 * f + c]);
+            if (a != b) parent[std::max(a, b)] = std::min(a, b);
+        }
+    std::vector<int32_t> label(P->nV), root_label(P->nV, -1);
+    int nc = 0;
+    for (int64_t v = 0; v < P->nV; ++v) {
+        int32_t r = find((int32_t)v);
+        if (root_label[r] < 0) root_label[r] = nc++;
+        label[v] = root_label[r];
+    }
+    if (nc > kMaxComponents)
+        return fail(TP_E_INVALID_ARGUMENT, "more than " + std::to_string(kMaxComponents) + " connected components");
+    std::vector<double> cnt(nc, 0.0);
+    for (int64_t v = 0; v < P->nV; ++v) cnt[label[v]] += 1.0;
+    for (auto& c : cnt) c = 1.0 / c;
+    P->ncomp = nc;
+    TP_TRY(P->comp.ensure(P->nV, s));
+    TP_TRY(P->inv_count.ensure(nc, s));
+    TP_HIP(hipMemcpyAsync(P->comp.p, label.data(), sizeof(int32_t) * P->nV, hipMemcpyHostToDevice, s));
+    TP_HIP(hipMemcpyAsync(P->inv_count.p, cnt.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
+    TP_HIP(hipStreamSynchronize(s));
+    P->have_lap = true;
+    return TP_OK;
+}
+
+tp_status ensure_cotan(tp_problem* P)
+{
+    TP_TRY(ensure_lap(P));
+    if (!P->cotan_valid) {
+        TP_HIP(launch_cotan_values(P->V.p, P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->lap_off.p,
+                                   P->lap_col.p, P->lap_val.p, P->stream));
+        P->cotan_valid = true;
+    }
+    return TP_OK;
+}
+
+// Sum of n doubles with stride ld (device), to the host.
+tp_status device_sum(tp_problem* P, const double* x, int ld, int64_t n, double* out)
+{
+    TP_HIP(launch_dot_cols(x, ld, nullptr, 0, n, 1, P->red.p, P->scal.p, P->stream));
+    return read_scalars(P, P->scal.p, out, 1);
+}
+
+// Total area (from the current face data, which must describe Vsrc) and signed volume.
+tp_status total_area_volume(tp_problem* P, const double* Vsrc, double* area, double* vol)
+{
+    // areas are the .w lane of the FP64 barycenter array
+    TP_TRY(device_sum(P, &P->dx.p[0].w, 4, P->nF, area));
+    TP_TRY(P->vol6.ensure(P->nF, P->stream));
+    TP_HIP(launch_face_volume(Vsrc, P->F.p, P->nF, P->vol6.p, P->stream));
+    double v6 = 0;
+    TP_TRY(device_sum(P, P->vol6.p, 1, P->nF, &v6));
+    *vol = v6 / 6.0;
+    return TP_OK;
+}
+
+// ------------------------------------------------------------------ energy / gradient
+
+bool finite(double x) { return std::isfinite(x); }
+
+tp_status run_energy(tp_problem* P, double* E)
+{
+    const PairPlan pl = plan_for(kKindEnergy, P->prm.precision, 1, P->nF, P->cap);
+    TP_TRY(P->part.ensure((size_t)pl.n_split * pl.irows, P->stream));
+    TP_TRY(P->gface.ensure((size_t)pl.irows, P->stream));
+    {
+        PairTimer t(kKindEnergy, (double)P->nF * (double)(P->nF - 1), 0.0, P->stream);
+        TP_HIP(launch_pairs_energy(P->fd, pl, P->prm.precision, P->prm.alpha, P->prm.beta, P->part.p, P->stream));
+        t.stop();
+    }
+    TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, 1, pl.irows, P->nF, P->gface.p, pl.irows, P->stream));
+    // E = sum_S a_S sum_T a_T K(S,T)
+    TP_HIP(launch_dot_cols(&P->dx.p[0].w, 4, P->gface.p, 1, P->nF, 1, P->red.p, P->scal.p, P->stream));
+    TP_TRY(read_scalars(P, P->scal.p, E, 1));
+    if (!finite(*E)) return fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
+    return TP_OK;
+}
+
+tp_status run_gradient(tp_problem* P, double* E, double* dE)
+{
+    TP_TRY(ensure_vf(P));
+    const PairPlan pl = plan_for(kKindGrad, P->prm.precision, 1, P->nF, P->cap);
+    TP_TRY(P->part.ensure((size_t)pl.n_split * 7 * pl.irows, P->stream));
+    TP_TRY(P->gface.ensure((size_t)7 * pl.irows, P->stream));
+    {
+        PairTimer t(kKindGrad, (double)P->nF * (double)(P->nF - 1), 0.0, P->stream);
+        TP_HIP(launch_pairs_grad(P->fd, pl, P->prm.precision, P->prm.alpha, P->prm.beta, P->part.p, P->stream));
+        t.stop();
+    }
+    TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, 7, pl.irows, P->nF, P->gface.p, pl.irows, P->stream));
+    TP_HIP(launch_grad_gather(P->V.p, P->F.p, P->nV, P->nF, P->vf_off.p, P->vf_idx.p, P->gface.p, pl.irows, dE, P->stream));
+    // E = (1/2) sum_S a_S dE/da_S, since dE/da_S = sum_T a_T (K(S,T) + K(T,S))
+    TP_HIP(launch_dot_cols(&P->dx.p[0].w, 4, P->gface.p + 6 * pl.irows, 1, P->nF, 1, P->red.p, P->scal.p, P->stream));
+    double twoE = 0;
+    TP_TRY(read_scalars(P, P->scal.p, &twoE, 1));
+    *E = 0.5 * twoE;
+    if (!finite(*E)) return fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
+    return TP_OK;
+}
+
+// Lu[:, c] for columns of u (row stride ldu) into Lu (row stride ldl), k columns.
+tp_status run_fractional(tp_problem* P, const double* u, int ldu, int k, double* Lu, int ldl)
+{
+    TP_TRY(ensure_vf(P));
+    const int prec = P->prm.precision;
+    const size_t esz = prec == TP_PREC_FP64 ? sizeof(double) : sizeof(float);
+    for (int c0 = 0; c0 < k; c0 += kMaxGroupCols) {
+        const int kc = std::min(kMaxGroupCols, k - c0);
+        const int kp = (kc + 3) / 4 * 4;
+        const PairPlan pl = plan_for(kKindFrac, prec, kc, P->nF, P->cap);
+        TP_TRY(P->ub.ensure((size_t)P->cap * kp * esz, P->stream));
+        TP_TRY(P->part.ensure((size_t)pl.n_split * kc * pl.irows, P->stream));
+        TP_TRY(P->zbuf.ensure((size_t)kc * pl.irows, P->stream));
+        // face averages of columns [c0, c0 + kc): pass a shifted pointer with stride ldu
+        TP_HIP(launch_face_avg(P->F.p, P->nF, P->cap, u + c0, ldu, kc, kp, prec, P->ub.p, P->stream));
+        {
+            PairTimer t(kKindFrac, (double)P->nF * (double)(P->nF - 1),
+                        (double)P->nF * (double)(P->nF - 1) * kc, P->stream);
+            TP_HIP(launch_pairs_frac(P->fd, pl, prec, P->sigma, P->ub.p, kc, kp, P->part.p, P->stream));
+            t.stop();
+        }
+        TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, kc, pl.irows, P->nF, P->zbuf.p, pl.irows, P->stream));
+        TP_HIP(launch_ut_gather(P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->fd, P->zbuf.p, pl.irows,
+                                kc, ldl, c0, Lu, P->stream));
+    }
+    return TP_OK;
+}
+
+tp_status ensure_cg(tp_problem* P, int k)
+{
+    hipStream_t s = P->stream;
+    TP_TRY(P->cg_r.ensure((size_t)P->nV * k, s));
+    TP_TRY(P->cg_q.ensure((size_t)P->nV * k, s));
+    TP_TRY(P->cg_p.ensure((size_t)2 * P->nV * k, s));
+    TP_TRY(P->cg_red.ensure(cg_red_doubles(k), s));
+    TP_TRY(P->cg_bar.ensure(cg_bar_words(k), s));
+    TP_TRY(P->cg_iters.ensure(std::max(k, 64), s));
+    TP_TRY(P->cg_relres.ensure(std::max(k, 64), s));
+    TP_TRY(P->red.ensure(std::max(reduce_scratch_doubles(16), project_scratch_doubles(k, P->ncomp)), s));
+    return TP_OK;
+}
+
+// x = C^+ b for k columns (row stride k); b is overwritten with its projection.
+tp_status run_cg(tp_problem* P, double* b, double* x, int k, int* it_max, double* res_max)
+{
+    TP_TRY(ensure_cotan(P));
+    TP_TRY(ensure_cg(P, k));
+    hipStream_t s = P->stream;
+    TP_HIP(launch_project_mean(b, k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
+    CgWork w;
+    w.r = P->cg_r.p; w.q = P->cg_q.p; w.p = P->cg_p.p; w.red = P->cg_red.p; w.bar = P->cg_bar.p;
+    w.iters = P->cg_iters.p; w.relres = P->cg_relres.p; w.flags = P->flags.p;
+    TP_HIP(launch_cg(P->nV, P->lap_off.p, P->lap_col.p, P->lap_val.p, b, x, k, P->prm.cg_rtol,
+                     P->prm.cg_maxiter, w, s));
+    TP_HIP(launch_project_mean(x, k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
+    std::vector<int> its(k);
+    std::vector<double> res(k);
+    TP_HIP(hipMemcpyAsync(its.data(), P->cg_iters.p, sizeof(int) * k, hipMemcpyDeviceToHost, s));
+    TP_HIP(hipMemcpyAsync(res.data(), P->cg_relres.p, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    TP_TRY(check_flags(P));   // synchronises
+    int im = 0;
+    double rm = 0;
+    for (int c = 0; c < k; ++c) {
+        im = std::max(im, its[c]);
+        rm = std::max(rm, res[c]);
+    }
+    *it_max = im;
+    *res_max = rm;
+    if (!(rm <= P->prm.cg_rtol)) return fail(TP_E_NOT_CONVERGED, "CG did not reach cg_rtol within cg_maxiter (relres " + std::to_string(rm) + ")");
+    return TP_OK;
+}
+
+struct EventTimer {
+    hipEvent_t e[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    hipStream_t s;
+    explicit EventTimer(hipStream_t s_) : s(s_)
+    {
+        for (auto& x : e) (void)hipEventCreate(&x);
+    }
+    void mark(int i) { (void)hipEventRecord(e[i], s); }
+    double ms(int i, int j)
+    {
+        float v = 0.f;
+        (void)hipEventSynchronize(e[j]);
+        (void)hipEventElapsedTime(&v, e[i], e[j]);
+        return v;
+    }
+    ~EventTimer()
+    {
+        for (auto& x : e)
+            if (x) (void)hipEventDestroy(x);
+    }
+};
+
+// x = A~^{-1} b columnwise, k columns, row stride k.  b is not modified.
+tp_status run_precond(tp_problem* P, const double* b, int k, double* x, tp_solve_report* rep)
+{
+    TP_TRY(ensure_geometry(P));
+    TP_TRY(ensure_lap(P));
+    hipStream_t s = P->stream;
+    const size_t nk = (size_t)P->nV * k;
+    TP_TRY(P->W1.ensure(nk, s));
+    TP_TRY(P->W2.ensure(nk, s));
+    EventTimer tm(s);
+    tm.mark(0);
+    TP_HIP(hipMemcpyAsync(P->W1.p, b, nk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int it1 = 0, it2 = 0;
+    double r1 = 0, r2 = 0;
+    tp_status st1 = run_cg(P, P->W1.p, P->W2.p, k, &it1, &r1);          // W2 = C^+ P b
+    if (st1 != TP_OK && st1 != TP_E_NOT_CONVERGED) return st1;
+    tm.mark(1);
+    TP_TRY(run_fractional(P, P->W2.p, k, k, P->W1.p, k));               // W1 = L W2
+    tm.mark(2);
+    tp_status st2 = run_cg(P, P->W1.p, x, k, &it2, &r2);                 // x = C^+ P W1
+    if (st2 != TP_OK && st2 != TP_E_NOT_CONVERGED) return st2;
+    tm.mark(3);
+    if (rep) {
+        rep->cg_iters[0] = it1;
+        rep->cg_iters[1] = it2;
+        rep->cg_relres[0] = r1;
+        rep->cg_relres[1] = r2;
+        rep->t_ms[0] = tm.ms(0, 1);
+        rep->t_ms[1] = tm.ms(1, 2);
+        rep->t_ms[2] = tm.ms(2, 3);
+        rep->t_ms[3] = tm.ms(0, 3);
+    } else {
+        TP_HIP(hipStreamSynchronize(s));
+    }
+    if (st1 != TP_OK) return st1;
+    return st2;
+}
+
+tp_status create_problem(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                         const tp_params* params, hipStream_t stream, tp_problem** out)
+{
+    if (!out) return fail(TP_E_INVALID_ARGUMENT, "out is NULL");
+    *out = nullptr;
+    if (!V || !F) return fail(TP_E_INVALID_ARGUMENT, "V and F must be non-NULL device pointers");
+    if (nV < 3 || nF < 2) return fail(TP_E_INVALID_ARGUMENT, "need nV >= 3 and nF >= 2");
+    if (nF > (int64_t)(INT32_MAX / 8) || nV > (int64_t)(INT32_MAX / 8))
+        return fail(TP_E_INVALID_ARGUMENT, "mesh too large for 32-bit indices");
+    auto* P = new tp_problem();
+    tp_status st = validate_params(params, P->prm, P->sigma);
+    if (st != TP_OK) {
+        delete P;
+        return st;
+    }
+    (void)hipGetDevice(&P->device);
+    P->stream = stream;
+    P->nV = nV;
+    P->nF = nF;
+    auto bail = [&](tp_status s) {
+        (void)hipStreamSynchronize(P->stream);
+        delete P;
+        return s;
+    };
+    if ((st = P->V.ensure(3 * nV, stream)) != TP_OK) return bail(st);
+    if ((st = P->F.ensure(3 * nF, stream)) != TP_OK) return bail(st);
+    if ((st = alloc_faces(P)) != TP_OK) return bail(st);
+    if (hipMemcpyAsync(P->V.p, V, sizeof(double) * 3 * nV, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+        hipMemcpyAsync(P->F.p, F, sizeof(int32_t) * 3 * nF, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+        return bail(fail(TP_E_DEVICE, "copy of V / F failed (are they device pointers?)"));
+    if (launch_check_indices(P->F.p, nF, nV, P->flags.p, stream) != hipSuccess)
+        return bail(fail(TP_E_DEVICE, "index check launch failed"));
+    if ((st = check_flags(P)) != TP_OK) return bail(st);
+    if ((st = geometry(P)) != TP_OK) return bail(st);
+    *out = P;
+    return TP_OK;
+}
+
+// Initial area, volume and mean edge length (targets and default step of the descent step).
+tp_status ensure_initial_measures(tp_problem* P)
+{
+    if (P->mean_edge > 0) return TP_OK;
+    TP_TRY(ensure_geometry(P));
+    TP_TRY(total_area_volume(P, P->V.p, &P->area0, &P->vol0));
+    TP_TRY(P->edge.ensure(P->nF, P->stream));
+    hipLaunchKernelGGL(k_face_edges, dim3((unsigned)((P->nF + 255) / 256)), dim3(256), 0, P->stream,
+                       P->V.p, P->F.p, P->nF, P->edge.p);
+    TP_HIP(hipGetLastError());
+    double es = 0;
+    TP_TRY(device_sum(P, P->edge.p, 1, P->nF, &es));
+    P->mean_edge = es / (3.0 * (double)P->nF);
+    return TP_OK;
+}
+
+struct HostSolve2 {
+    // solve the k x k system S z = r (k <= 2)
+    static bool solve(int k, const double S[4], const double* r, double* z)
+    {
+        if (k == 0) return true;
+        if (k == 1) {
+            if (!(std::fabs(S[0]) > 0)) return false;
+            z[0] = r[0] / S[0];
+            return std::isfinite(z[0]);
+        }
+        const double det = S[0] * S[3] - S[1] * S[2];
+        const double scale = std::fabs(S[0] * S[3]) + std::fabs(S[1] * S[2]);
+        if (!(std::fabs(det) > 1e-14 * scale)) return false;
+        z[0] = (S[3] * r[0] - S[1] * r[1]) / det;
+        z[1] = (S[0] * r[1] - S[2] * r[0]) / det;
+        return std::isfinite(z[0]) && std::isfinite(z[1]);
+    }
+};
+
+tp_status run_step(tp_problem* P, const tp_step_opts* opts_in, tp_step_report* rep, double* dir_out)
+{
+    tp_step_opts o;
+    tp_step_opts_default(&o);
+    if (opts_in) o = *opts_in;
+    if (!(o.shrink > 0.0 && o.shrink < 1.0)) return fail(TP_E_INVALID_ARGUMENT, "shrink must lie in (0, 1)");
+    if (o.max_backtracks < 0) return fail(TP_E_INVALID_ARGUMENT, "max_backtracks must be >= 0");
+    hipStream_t s = P->stream;
+    const int64_t n = P->nV;
+    tp_step_report R;
+    std::memset(&R, 0, sizeof(R));
+    EventTimer tm(s);
+    TP_TRY(ensure_initial_measures(P));
+    TP_TRY(ensure_geometry(P));
+    TP_TRY(ensure_cotan(P));
+    const double A0 = std::isnan(o.area_target) ? P->area0 : o.area_target;
+    const double V0 = std::isnan(o.volume_target) ? P->vol0 : o.volume_target;
+    const int kc = (o.constrain_area ? 1 : 0) + (o.constrain_volume ? 1 : 0);
+    const int ncol = 3 * (1 + kc);
+    TP_TRY(P->R.ensure((size_t)n * ncol, s));
+    TP_TRY(P->Y.ensure((size_t)n * ncol, s));
+    TP_TRY(P->gbuf.ensure((size_t)n * 3, s));
+    TP_TRY(P->dir.ensure((size_t)n * 3, s));
+    TP_TRY(P->Vt.ensure((size_t)n * 3, s));
+    TP_TRY(P->scal.ensure(256, s));
+
+    // 1. g = dE
+    tm.mark(0);
+    double E0 = 0;
+    TP_TRY(run_gradient(P, &E0, P->gbuf.p));
+    TP_HIP(launch_copy_cols(n, P->gbuf.p, 3, 3, P->R.p, ncol, s));
+    // 2. constraint rows: area gradient = C f (twice the mean curvature normal), volume gradient
+    int col = 3;
+    if (o.constrain_area) {
+        TP_HIP(launch_spmm(n, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->V.p, 3, 3, P->R.p + col, ncol, s));
+        col += 3;
+    }
+    if (o.constrain_volume) {
+        TP_HIP(launch_volume_gradient(P->V.p, P->F.p, n, P->vf_off.p, P->vf_idx.p, P->R.p, ncol, col, s));
+        col += 3;
+    }
+    tm.mark(1);
+    // 3. Y = A~^{-1} [g | J^T]
+    tp_solve_report sr;
+    tp_status pst = run_precond(P, P->R.p, ncol, P->Y.p, &sr);
+    if (pst != TP_OK && pst != TP_E_NOT_CONVERGED) return pst;
+    R.cg_iters[0] = sr.cg_iters[0];
+    R.cg_iters[1] = sr.cg_iters[1];
+    R.cg_relres[0] = sr.cg_relres[0];
+    R.cg_relres[1] = sr.cg_relres[1];
+    tm.mark(2);
+    // 4. Schur system S = J Y (k x k), rhs = J y_g
+    double Sm[4] = {0, 0, 0, 0}, rhs[2] = {0, 0}, mu[2] = {0, 0};
+    {
+        std::vector<double> h(3);
+        for (int a = 0; a < kc; ++a) {
+            for (int b2 = 0; b2 < kc; ++b2) {
+                TP_HIP(launch_dot_cols(P->R.p + 3 * (1 + a), ncol, P->Y.p + 3 * (1 + b2), ncol, n, 3, P->red.p, P->scal.p, s));
+                TP_TRY(read_scalars(P, P->scal.p, h.data(), 3));
+                Sm[a * kc + b2] = h[0] + h[1] + h[2];
+            }
+            TP_HIP(launch_dot_cols(P->R.p + 3 * (1 + a), ncol, P->Y.p, ncol, n, 3, P->red.p, P->scal.p, s));
+            TP_TRY(read_scalars(P, P->scal.p, h.data(), 3));
+            rhs[a] = h[0] + h[1] + h[2];
+        }
+        if (!HostSolve2::solve(kc, Sm, rhs, mu))
+            return fail(TP_E_SINGULAR_CONSTRAINTS, "Schur complement J A~^{-1} J^T is singular");
+    }
+    // x = -(y_g - Y S^{-1} J y_g)
+    {
+        double cf[2] = {mu[0], mu[1]};
+        int cols[2] = {3, 6};
+        TP_HIP(launch_axpy_block3(n, P->Y.p, ncol, -1.0, P->Y.p, ncol, kc, cf, cols, P->dir.p, 3, s));
+    }
+    double gg[3], gx[3];
+    TP_HIP(launch_dot_cols(P->gbuf.p, 3, P->gbuf.p, 3, n, 3, P->red.p, P->scal.p, s));
+    TP_TRY(read_scalars(P, P->scal.p, gg, 3));
+    TP_HIP(launch_dot_cols(P->gbuf.p, 3, P->dir.p, 3, n, 3, P->red.p, P->scal.p, s));
+    TP_TRY(read_scalars(P, P->scal.p, gx, 3));
+    const double slope = gx[0] + gx[1] + gx[2];
+    R.E = E0;
+    R.grad_norm = std::sqrt(gg[0] + gg[1] + gg[2]);
+    R.slope = slope;
+    R.n_constraints = kc;
+    tm.mark(3);
+
+    // Constraint values at f
+    {
+        double a = 0, v = 0;
+        TP_TRY(total_area_volume(P, P->V.p, &a, &v));
+        int m = 0;
+        if (o.constrain_area) R.phi_before[m++] = a - A0;
+        if (o.constrain_volume) R.phi_before[m++] = v - V0;
+    }
+
+    // 5. Armijo line search on E(f + tau x)
+    double tau = o.tau0;
+    if (!(tau > 0)) {
+        double mx = 0;
+        TP_HIP(launch_max_rownorm3(P->dir.p, n, P->red.p, P->scal.p, s));
+        TP_TRY(read_scalars(P, P->scal.p, &mx, 1));
+        if (!(mx > 0)) return fail(TP_E_NONFINITE, "zero or non-finite descent direction");
+        tau = 0.5 * P->mean_edge / mx;
+    }
+    int bt = 0;
+    double Et = 0;
+    for (;;) {
+        const double cf = tau;
+        const int c0 = 0;
+        TP_HIP(launch_axpy_block3(n, P->V.p, 3, 1.0, P->dir.p, 3, 1, &cf, &c0, P->Vt.p, 3, s));
+        tp_status gs = geometry(P, P->Vt.p);
+        if (gs != TP_OK && gs != TP_E_DEGENERATE_FACE && gs != TP_E_NONFINITE) return gs;
+        bool ok = false;
+        if (gs == TP_OK) {
+            tp_status es = run_energy(P, &Et);
+            if (es != TP_OK && es != TP_E_NONFINITE) return es;
+            ok = (es == TP_OK) && (!o.line_search || Et <= E0 + o.armijo_c * tau * slope);
+        }
+        if (ok || !o.line_search) {
+            if (!ok) return fail(TP_E_NONFINITE, "the fixed step produces a degenerate mesh");
+            break;
+        }
+        if (bt >= o.max_backtracks) {
+            if (gs != TP_OK) return fail(TP_E_NONFINITE, "line search found no valid step");
+            break;
+        }
+        tau *= o.shrink;
+        ++bt;
+    }
+    R.tau = tau;
+    R.backtracks = bt;
+    tm.mark(4);
+
+    // 6. Corrective projection h = -Y S^{-1} Phi(f + tau x) (geometry now describes Vt)
+    double phi[2] = {0, 0};
+    {
+        double a = 0, v = 0;
+        TP_TRY(total_area_volume(P, P->Vt.p, &a, &v));
+        int m = 0;
+        if (o.constrain_area) phi[m++] = a - A0;
+        if (o.constrain_volume) phi[m++] = v - V0;
+        R.phi_trial[0] = phi[0];
+        R.phi_trial[1] = phi[1];
+    }
+    double lam[2] = {0, 0};
+    if (kc > 0 && !HostSolve2::solve(kc, Sm, phi, lam))
+        return fail(TP_E_SINGULAR_CONSTRAINTS, "Schur complement is singular");
+    {
+        double cf[2] = {-lam[0], -lam[1]};
+        int cols[2] = {3, 6};
+        TP_HIP(launch_axpy_block3(n, P->Vt.p, 3, 1.0, P->Y.p, ncol, kc, cf, cols, P->V.p, 3, s));
+    }
+    if (dir_out) TP_HIP(hipMemcpyAsync(dir_out, P->dir.p, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    P->cotan_valid = false;
+    P->geom_valid = false;
+    TP_TRY(geometry(P));
+    {
+        double a = 0, v = 0;
+        TP_TRY(total_area_volume(P, P->V.p, &a, &v));
+        int m = 0;
+        if (o.constrain_area) R.phi_after[m++] = a - A0;
+        if (o.constrain_volume) R.phi_after[m++] = v - V0;
+    }
+    TP_TRY(run_energy(P, &R.E_new));
+    tm.mark(5);
+    R.t_ms[0] = tm.ms(0, 1);
+    R.t_ms[2] = tm.ms(1, 2);
+    R.t_ms[3] = tm.ms(2, 3);
+    R.t_ms[4] = tm.ms(3, 4);
+    R.t_ms[5] = tm.ms(4, 5);
+    R.t_ms[6] = tm.ms(0, 5);
+    if (rep) *rep = R;
+    return pst;
+}
+
+struct ProblemGuard {
+    tp_problem* p = nullptr;
+    ~ProblemGuard()
+    {
+        if (p) tp_problem_destroy(p);
+    }
+};
+
+tp_status bind(tp_problem* P)
+{
+    if (!P) return fail(TP_E_INVALID_ARGUMENT, "problem is NULL");
+    TP_HIP(hipSetDevice(P->device));
+    return TP_OK;
+}
+
+}  // namespace
+
+// ======================================================================== C-ABI
+
+extern "C" {
+
+tp_status tp_params_default(tp_params* p)
+{
+    if (!p) return TP_E_INVALID_ARGUMENT;
+    p->alpha = 6.0;
+    p->beta = 12.0;
+    p->sigma = -1.0;
+    p->precision = TP_PREC_FP32_HILO;
+    p->cg_rtol = 1e-10;
+    p->cg_maxiter = 20000;
+    return TP_OK;
+}
+
+tp_status tp_step_opts_default(tp_step_opts* o)
+{
+    if (!o) return TP_E_INVALID_ARGUMENT;
+    o->tau0 = 0.0;
+    o->line_search = 1;
+    o->armijo_c = 1e-4;
+    o->shrink = 0.5;
+    o->max_backtracks = 30;
+    o->constrain_area = 1;
+    o->constrain_volume = 1;
+    o->area_target = NAN;
+    o->volume_target = NAN;
+    return TP_OK;
+}
+
+const char* tp_last_error(void) { return get_error(); }
+
+tp_status tp_problem_create(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                            const tp_params* params, void* stream, tp_problem** out)
+{
+    set_error("");
+    return create_problem(V, nV, F, nF, params, (hipStream_t)stream, out);
+}
+
+void tp_problem_destroy(tp_problem* prob)
+{
+    if (!prob) return;
+    (void)hipSetDevice(prob->device);
+    (void)hipStreamSynchronize(prob->stream);
+    delete prob;
+}
+
+tp_status tp_problem_set_vertices(tp_problem* P, const double* V)
+{
+    TP_TRY(bind(P));
+    if (!V) return fail(TP_E_INVALID_ARGUMENT, "V is NULL");
+    TP_HIP(hipMemcpyAsync(P->V.p, V, sizeof(double) * 3 * P->nV, hipMemcpyDeviceToDevice, P->stream));
+    P->geom_valid = false;
+    P->cotan_valid = false;
+    return geometry(P);
+}
+
+tp_status tp_problem_get_vertices(tp_problem* P, double* V_out)
+{
+    TP_TRY(bind(P));
+    if (!V_out) return fail(TP_E_INVALID_ARGUMENT, "V_out is NULL");
+    TP_HIP(hipMemcpyAsync(V_out, P->V.p, sizeof(double) * 3 * P->nV, hipMemcpyDeviceToDevice, P->stream));
+    TP_HIP(hipStreamSynchronize(P->stream));
+    return TP_OK;
+}
+
+tp_status tp_problem_energy(tp_problem* P, double* E_out)
+{
+    TP_TRY(bind(P));
+    if (!E_out) return fail(TP_E_INVALID_ARGUMENT, "E_out is NULL");
+    set_error("");
+    TP_TRY(ensure_geometry(P));
+    return run_energy(P, E_out);
+}
+
+tp_status tp_problem_gradient(tp_problem* P, double* E_out, double* dE_out)
+{
+    TP_TRY(bind(P));
+    if (!E_out || !dE_out) return fail(TP_E_INVALID_ARGUMENT, "E_out and dE_out must be non-NULL");
+    set_error("");
+    TP_TRY(ensure_geometry(P));
+    TP_TRY(run_gradient(P, E_out, dE_out));
+    TP_HIP(hipStreamSynchronize(P->stream));
+    return TP_OK;
+}
+
+tp_status tp_problem_fractional_apply(tp_problem* P, const double* u, int k, double* Lu_out)
+{
+    TP_TRY(bind(P));
+    if (!u || !Lu_out) return fail(TP_E_INVALID_ARGUMENT, "u and Lu_out must be non-NULL");
+    if (k < 1 || k > kMaxCols) return fail(TP_E_INVALID_ARGUMENT, "k must lie in [1, 64]");
+    set_error("");
+    TP_TRY(ensure_geometry(P));
+    TP_TRY(run_fractional(P, u, k, k, Lu_out, k));
+    TP_HIP(hipStreamSynchronize(P->stream));
+    return TP_OK;
+}
+
+tp_status tp_problem_precond_apply(tp_problem* P, const double* b, int k, double* x_out,
+                                   tp_solve_report* report)
+{
+    TP_TRY(bind(P));
+    if (!b || !x_out) return fail(TP_E_INVALID_ARGUMENT, "b and x_out must be non-NULL");
+    if (k < 1 || k > kMaxCols) return fail(TP_E_INVALID_ARGUMENT, "k must lie in [1, 64]");
+    set_error("");
+    return run_precond(P, b, k, x_out, report);
+}
+
+tp_status tp_precond_step(tp_problem* P, const tp_step_opts* opts, tp_step_report* report,
+                          double* direction_out)
+{
+    TP_TRY(bind(P));
+    set_error("");
+    return run_step(P, opts, report, direction_out);
+}
+
+tp_status tp_energy(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                    const tp_params* params, double* E_out, void* stream)
+{
+    if (!E_out) return fail(TP_E_INVALID_ARGUMENT, "E_out is NULL");
+    ProblemGuard g;
+    TP_TRY(tp_problem_create(V, nV, F, nF, params, stream, &g.p));
+    return run_energy(g.p, E_out);
+}
+
+tp_status tp_gradient(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                      const tp_params* params, double* E_out, double* dE_out, void* stream)
+{
+    ProblemGuard g;
+    TP_TRY(tp_problem_create(V, nV, F, nF, params, stream, &g.p));
+    return tp_problem_gradient(g.p, E_out, dE_out);
+}
+
+tp_status tp_fractional_apply(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                              const tp_params* params, const double* u, int k, double* Lu_out,
+                              void* stream)
+{
+    if (k < 1 || k > kMaxCols) return fail(TP_E_INVALID_ARGUMENT, "k must lie in [1, 64]");
+    ProblemGuard g;
+    TP_TRY(tp_problem_create(V, nV, F, nF, params, stream, &g.p));
+    return tp_problem_fractional_apply(g.p, u, k, Lu_out);
+}
+
+tp_status tp_precond_apply(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                           const tp_params* params, const double* b, int k, double* x_out,
+                           tp_solve_report* report, void* stream)
+{
+    if (k < 1 || k > kMaxCols) return fail(TP_E_INVALID_ARGUMENT, "k must lie in [1, 64]");
+    ProblemGuard g;
+    TP_TRY(tp_problem_create(V, nV, F, nF, params, stream, &g.p));
+    return tp_problem_precond_apply(g.p, b, k, x_out, report);
+}
+
+tp_status tp_energy_faces(const double* X, const double* N, const double* a, int64_t nF,
+                          const tp_params* params, double* E_out, void* stream)
+{
+    set_error("");
+    if (!X || !N || !a || !E_out) return fail(TP_E_INVALID_ARGUMENT, "NULL argument");
+    if (nF < 2 || nF > (int64_t)(INT32_MAX / 8)) return fail(TP_E_INVALID_ARGUMENT, "need 2 <= nF < 2^28");
+    auto* P = new tp_problem();
+    ProblemGuard g;
+    g.p = P;
+    TP_TRY(validate_params(params, P->prm, P->sigma));
+    (void)hipGetDevice(&P->device);
+    P->stream = (hipStream_t)stream;
+    P->nF = nF;
+    P->nV = 0;
+    TP_TRY(alloc_faces(P));
+    TP_HIP(launch_face_from_quantities(X, N, a, nF, P->fd, P->flags.p, P->stream));
+    TP_TRY(check_flags(P));
+    return run_energy(P, E_out);
+}
+
+tp_status tp_profile_enable(int on)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    return TP_OK;
+}
+
+tp_status tp_profile_reset(void)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (auto& s : g_prof.st) std::memset(&s, 0, sizeof(s));
+    return TP_OK;
+}
+
+tp_status tp_profile_get(int kind, tp_kernel_stats* out)
+{
+    if (kind < 0 || kind > 2 || !out) return TP_E_INVALID_ARGUMENT;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    *out = g_prof.st[kind];
+    return TP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+// Internal declarations shared by the tpsurf HIP sources (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/tpsurf.h"
+
+namespace tp {
+
+// ------------------------------------------------------------------ constants
+
+constexpr int kBlock = 256;        // threads per workgroup of the pair kernels
+constexpr int kTileJ = 128;        // T faces staged in LDS per tile
+constexpr int kMaxCols = 64;       // largest k accepted by the column-batched calls
+constexpr int kMaxGroupCols = 9;   // columns handled by one pair / CG kernel instance
+constexpr int kMaxComponents = 4096;
+
+// Kinds for the kernel timing statistics.
+enum PairKind { kKindEnergy = 0, kKindGrad = 1, kKindFrac = 2 };
+
+// Error flags written by device kernels (one int per condition, plain stores of 1).
+enum DevFlag { kFlagBadIndex = 0, kFlagDegenerate = 1, kFlagNonFinite = 2, kFlagCgAbort = 3,
+               kNumFlags = 4 };
+
+// ------------------------------------------------------------------ error helpers
+
+void set_error(const std::string& msg);
+const char* get_error();
+
+#define TP_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::tp::set_error(std::string(#call) + ": " + hipGetErrorString(e_));        \
+            return TP_E_DEVICE;                                                        \
+        }                                                                              \
+    } while (0)
+
+#define TP_TRY(expr)                                                                   \
+    do {                                                                               \
+        tp_status s_ = (expr);                                                         \
+        if (s_ != TP_OK) return s_;                                                    \
+    } while (0)
+
+// ------------------------------------------------------------------ device info
+
+struct DeviceInfo {
+    int device = -1;
+    int num_cu = 0;
+    int max_threads_per_cu = 0;
+};
+const DeviceInfo& device_info();
+
+// ------------------------------------------------------------------ face data
+
+// Face quantities for the pair kernels.  Arrays hold `cap` entries; entries past nF are
+// padding faces placed far away with zero area and zero normal, so every tile is full.
+struct FaceData {
+    int64_t nF = 0, cap = 0;
+    float4* fx = nullptr;    // (Xhi.x, Xhi.y, Xhi.z, a)  FP32
+    float4* fl = nullptr;    // (Xlo.x, Xlo.y, Xlo.z, 0)  FP32, Xlo = X - Xhi rounded
+    float4* fn = nullptr;    // (N.x, N.y, N.z, 0)        FP32
+    double4* dx = nullptr;   // (X.x, X.y, X.z, a)        FP64
+    double4* dn = nullptr;   // (N.x, N.y, N.z, 0)        FP64
+};
+
+// Pair-kernel launch geometry for one problem size.
+struct PairPlan {
+    int ni = 2;              // i faces per thread
+    int n_itiles = 0;        // workgroups along i
+    int ntiles_j = 0;        // LDS tiles along j (cap / kTileJ)
+    int tiles_per_split = 0;
+    int n_split = 0;         // workgroups along j
+    int64_t irows = 0;       // n_itiles * kBlock * ni (row stride of the partial buffers)
+};
+
+// ------------------------------------------------------------------ kernels (launchers)
+
+// Face geometry from vertices and faces (FP64), written in FP32 hi/lo and FP64 forms.
+hipError_t launch_face_geom(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                            const FaceData& fd, int* flags, hipStream_t s);
+// Face data from caller-given face quantities (X, N row-major nF x 3, a nF).
+hipError_t launch_face_from_quantities(const double* X, const double* N, const double* a,
+                                       int64_t nF, const FaceData& fd, int* flags, hipStream_t s);
+
+int64_t face_capacity(int64_t nF, int ni_max);
+PairPlan plan_pairs(int64_t nF, int64_t cap, int ni, int occupancy_per_cu);
+
+// All-pairs kernels.  Partial buffers are [n_split][nacc][irows] doubles.
+hipError_t launch_pairs_energy(const FaceData& fd, const PairPlan& pl, int precision,
+                               double alpha, double beta, double* part, hipStream_t s);
+hipError_t launch_pairs_grad(const FaceData& fd, const PairPlan& pl, int precision,
+                             double alpha, double beta, double* part, hipStream_t s);
+// ub: face-averaged columns, FP32 [cap][kp] (kp = k rounded up to 4) or FP64 [cap][kp].
+hipError_t launch_pairs_frac(const FaceData& fd, const PairPlan& pl, int precision,
+                             double sigma, const void* ub, int k, int kp, double* part,
+                             hipStream_t s);
+PairPlan plan_for(int kind, int precision, int k, int64_t nF, int64_t cap);
+
+// Sum the n_split partials of every accumulator in split order: out[acc][i].
+hipError_t launch_reduce_splits(const double* part, int n_split, int nacc, int64_t irows,
+                                int64_t n, double* out, int64_t out_stride, hipStream_t s);
+
+// Mesh / sparse kernels.
+hipError_t launch_check_indices(const int32_t* F, int64_t nF, int64_t nV, int* flags, hipStream_t s);
+hipError_t launch_vf_count(const int32_t* F, int64_t nF, int64_t nV, int32_t* deg, hipStream_t s);
+hipError_t launch_scan(const int32_t* in, int64_t n, int32_t* out_excl /* n + 1 */, hipStream_t s);
+hipError_t launch_vf_fill(const int32_t* F, int64_t nF, int64_t nV, const int32_t* off,
+                          int32_t* cursor, int32_t* idx, hipStream_t s);
+hipError_t launch_sort_rows(const int32_t* off, int64_t n, int32_t* idx, hipStream_t s);
+hipError_t launch_lap_pattern_count(const int32_t* F, int64_t nV, const int32_t* vf_off,
+                                    const int32_t* vf_idx, int32_t* cand, int32_t* cnt,
+                                    hipStream_t s);
+hipError_t launch_lap_pattern_fill(int64_t nV, const int32_t* vf_off, const int32_t* cand,
+                                   const int32_t* lap_off, int32_t* lap_col, hipStream_t s);
+hipError_t launch_cotan_values(const double* V, const int32_t* F, int64_t nV,
+                               const int32_t* vf_off, const int32_t* vf_idx,
+                               const int32_t* lap_off, const int32_t* lap_col, double* lap_val,
+                               hipStream_t s);
+hipError_t launch_grad_gather(const double* V, const int32_t* F, int64_t nV, int64_t nF,
+                              const int32_t* vf_off, const int32_t* vf_idx,
+                              const double* gface, int64_t gstride, double* dE, hipStream_t s);
+// ubar of columns u[:, 0..k) (row stride ldu) into ub [cap][kp].
+hipError_t launch_face_avg(const int32_t* F, int64_t nF, int64_t cap, const double* u, int ldu,
+                           int k, int kp, int precision, void* ub, hipStream_t s);
+hipError_t launch_ut_gather(const int32_t* F, int64_t nV, const int32_t* vf_off,
+                            const int32_t* vf_idx, const FaceData& fd, const double* z,
+                            int64_t zstride, int k, int kout, int c0, double* Lu, hipStream_t s);
+hipError_t launch_volume_gradient(const double* V, const int32_t* F, int64_t nV,
+                                  const int32_t* vf_off, const int32_t* vf_idx, double* out,
+                                  int ldo, int c0, hipStream_t s);
+hipError_t launch_face_volume(const double* V, const int32_t* F, int64_t nF, double* vol6,
+                              hipStream_t s);
+hipError_t launch_spmm(int64_t n, const int32_t* off, const int32_t* col, const double* val,
+                       const double* x, int ldx, int k, double* y, int ldy, hipStream_t s);
+
+// Deterministic reductions.  `scratch` must hold reduce_scratch_doubles() doubles.
+size_t reduce_scratch_doubles(int ncols);
+// out[c] = sum_i x[i*ldx + c] * (y ? y[i*ldy + c] : 1) for c < ncols, written to device out.
+hipError_t launch_dot_cols(const double* x, int ldx, const double* y, int ldy, int64_t n,
+                           int ncols, double* scratch, double* out, hipStream_t s);
+// out = max_i |x_i| over n rows of 3 (Euclidean row norms), device scalar.
+hipError_t launch_max_rownorm3(const double* x, int64_t n, double* scratch, double* out,
+                               hipStream_t s);
+// Per-component means of k columns, then x -= mean[comp].
+hipError_t launch_project_mean(double* x, int ldx, int k, int64_t n, const int32_t* comp,
+                               const double* inv_count, int ncomp, double* scratch,
+                               hipStream_t s);
+size_t project_scratch_doubles(int k, int ncomp);
+
+// y = a*x + b*y style updates on n x 3 blocks: out = x + sum_m coef[m] * Y[:, cols_m].
+hipError_t launch_axpy_block3(int64_t n, const double* x, int ldx, double a,
+                              const double* Y, int ldy, int ncoef, const double* coef_host,
+                              const int* cols_host, double* out, int ldo, hipStream_t s);
+hipError_t launch_copy_cols(int64_t n, const double* x, int ldx, int k, double* y, int ldy,
+                            hipStream_t s);
+
+// Persistent FP64 conjugate gradients on k columns (row-major [n][k]).  x gets the
+// solution of C x = b (b must be per-component mean zero); iters / relres per column
+// are written to device arrays.  Work arrays: r, q [n][k]; p two buffers [2][n][k].
+struct CgWork {
+    double* r = nullptr;
+    double* q = nullptr;
+    double* p = nullptr;        // 2 * n * k
+    double* red = nullptr;      // reduction scratch
+    unsigned* bar = nullptr;    // barrier words
+    int* iters = nullptr;       // k
+    double* relres = nullptr;   // k
+    int* flags = nullptr;       // device error flags
+};
+size_t cg_red_doubles(int k);
+size_t cg_bar_words(int k);
+hipError_t launch_cg(int64_t n, const int32_t* off, const int32_t* col, const double* val,
+                     const double* b, double* x, int k, double rtol, int maxiter,
+                     const CgWork& w, hipStream_t s);
+
+}  // namespace tp

@@ -1,0 +1,851 @@
+// All-pairs face-face kernels of the tangent-point hot path (gfx950).
+//
+// Every kernel has the same shape: a workgroup owns an i-tile of kBlock * NI faces S
+// held in registers (NI per thread) and streams a contiguous range of j-tiles of kTileJ
+// faces T through LDS; every lane reads the same T (LDS broadcast).  The grid is
+// (i-tiles) x (j-splits); each workgroup writes its per-face sums for its j-range to a
+// partial buffer, and a separate pass adds the splits in order, so results do not depend
+// on scheduling.  The diagonal S = T is excluded by forcing |d|^2 = 1 where d = 0, which
+// makes every term vanish; only tiles that intersect the i-range take that check.
+//
+// Arithmetic (FP32 variants): pair terms in FP32 on the vector ALUs, per-tile sums in
+// FP32 over kTileJ terms, then added into FP64 accumulators.  With HILO the barycenter
+// difference is formed as (Xhi_S - Xhi_T) + (Xlo_S - Xlo_T) from an FP32 hi/lo split of
+// the FP64 barycenter, which keeps d accurate for near pairs (the kernel raises q = N.d
+// to the 6th power, and q is small for near pairs on a smooth surface).
+#include "tp_internal.h"
+
+#include <algorithm>
+#include <mutex>
+#include <unordered_map>
+
+namespace tp {
+
+// ------------------------------------------------------------------ fast math helpers
+
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_fast(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);       // v_rcp_f64, refined by two Newton steps
+    double e = __builtin_fma(-x, y, 1.0);
+    y = __builtin_fma(y, e, y);
+    e = __builtin_fma(-x, y, 1.0);
+    return __builtin_fma(y, e, y);
+}
+__device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// ------------------------------------------------------------------ exponent policies
+//
+// Kernel of eq. DiscreteTangentPointKernel with q = N_S . d, r2 = |d|^2:
+//   K   = |q|^alpha r2^(-beta/2)
+//   Kqr = K r2 / q = sgn(q) |q|^(alpha-1) r2^(1 - beta/2)   (0 when q = 0, alpha > 1)
+// so that dK/dd = alpha (Kqr / r2) N_S - beta (K / r2) d  and  dK/dN_S = alpha (Kqr / r2) d.
+
+// alpha = 6, beta = 12 (p = 6, Sec. 2.1): with u = q / r2, K = u^6 and Kqr = u^5.
+struct PowP6 {
+    template <class R>
+    __device__ __forceinline__ R K(R q, R r2, R inv) const
+    {
+        (void)r2;
+        R u = q * inv;
+        R u2 = u * u;
+        return u2 * u2 * u2;
+    }
+    template <class R>
+    __device__ __forceinline__ void KG(R q, R r2, R inv, R& K, R& Kqr) const
+    {
+        (void)r2;
+        R u = q * inv;
+        R u2 = u * u;
+        R u4 = u2 * u2;
+        K = u4 * u2;
+        Kqr = u4 * u;
+    }
+};
+
+// General exponents through log2 / exp2.
+struct PowGen {
+    float am1;      // alpha - 1
+    float hb;       // beta / 2
+    double am1d, hbd;
+    __device__ __forceinline__ float K(float q, float r2, float inv) const
+    {
+        (void)inv;
+        float lq = log2_fast(fabsf(q));
+        return exp2_fast((am1 + 1.0f) * lq - hb * log2_fast(r2));
+    }
+    __device__ __forceinline__ void KG(float q, float r2, float inv, float& K, float& Kqr) const
+    {
+        (void)inv;
+        float e = am1 * log2_fast(fabsf(q)) + (1.0f - hb) * log2_fast(r2);
+        Kqr = copysignf(exp2_fast(e), q);
+        K = Kqr * q * inv;
+    }
+    __device__ __forceinline__ double K(double q, double r2, double inv) const
+    {
+        (void)inv;
+        return pow(fabs(q), am1d + 1.0) * pow(r2, -hbd);
+    }
+    __device__ __forceinline__ void KG(double q, double r2, double inv, double& K, double& Kqr) const
+    {
+        Kqr = copysign(pow(fabs(q), am1d) * pow(r2, 1.0 - hbd), q);
+        K = Kqr * q * inv;
+    }
+};
+
+// ------------------------------------------------------------------ tile loading
+
+template <bool HILO>
+__device__ __forceinline__ void load_tile3(const float4* __restrict__ fx, const float4* __restrict__ fl,
+                                           const float4* __restrict__ fn, float4* s_x, float4* s_l,
+                                           float4* s_n, int64_t j0)
+{
+    constexpr int parts = HILO ? 3 : 2;
+    for (int e = threadIdx.x; e < parts * kTileJ; e += kBlock) {
+        int w = e / kTileJ, jj = e - w * kTileJ;
+        if (w == 0) s_x[jj] = fx[j0 + jj];
+        else if (w == 1) s_n[jj] = fn[j0 + jj];
+        else s_l[jj] = fl[j0 + jj];
+    }
+}
+
+__device__ __forceinline__ bool tile_hits_diag(int64_t j0, int64_t ibase, int ispan)
+{
+    return j0 < ibase + ispan && j0 + kTileJ > ibase;
+}
+
+// ============================================================== energy (FP32)
+
+template <bool DIAG, int NI, bool HILO, class Pow>
+__device__ __forceinline__ void energy_tile32(const float4* s_x, const float4* s_l, int64_t j0,
+                                              const float3 (&Sh)[NI], const float3 (&Sl)[NI],
+                                              const float3 (&Sn)[NI], const int64_t (&Si)[NI],
+                                              const Pow& pw, float (&c)[NI])
+{
+#pragma unroll 4
+    for (int jj = 0; jj < kTileJ; ++jj) {
+        const float4 tx = s_x[jj];
+        float4 tl = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (HILO) tl = s_l[jj];
+#pragma unroll
+        for (int r = 0; r < NI; ++r) {
+            float dx, dy, dz;
+            if (HILO) {
+                dx = (Sh[r].x - tx.x) + (Sl[r].x - tl.x);
+                dy = (Sh[r].y - tx.y) + (Sl[r].y - tl.y);
+                dz = (Sh[r].z - tx.z) + (Sl[r].z - tl.z);
+            } else {
+                dx = Sh[r].x - tx.x;
+                dy = Sh[r].y - tx.y;
+                dz = Sh[r].z - tx.z;
+            }
+            float r2 = dx * dx + dy * dy + dz * dz;
+            if (DIAG) r2 = (Si[r] == j0 + jj) ? 1.0f : r2;
+            const float inv = rcp_fast(r2);
+            const float q = Sn[r].x * dx + Sn[r].y * dy + Sn[r].z * dz;
+            c[r] += pw.K(q, r2, inv) * tx.w;
+        }
+    }
+}
+
+template <int NI, bool HILO, class Pow>
+__global__ __launch_bounds__(kBlock) void k_energy32(const float4* __restrict__ fx,
+                                                     const float4* __restrict__ fl,
+                                                     const float4* __restrict__ fn,
+                                                     int tiles_per_split, int ntiles_j, Pow pw,
+                                                     double* __restrict__ part, int64_t irows)
+{
+    __shared__ float4 s_x[kTileJ], s_l[HILO ? kTileJ : 1], s_n[kTileJ];
+    const int64_t ibase = (int64_t)blockIdx.x * (kBlock * NI);
+    const int jt0 = blockIdx.y * tiles_per_split;
+    const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
+    float3 Sh[NI], Sl[NI], Sn[NI];
+    int64_t Si[NI];
+    double acc[NI];
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+        Si[r] = ibase + r * kBlock + threadIdx.x;
+        float4 x = fx[Si[r]], n = fn[Si[r]];
+        Sh[r] = make_float3(x.x, x.y, x.z);
+        Sn[r] = make_float3(n.x, n.y, n.z);
+        if (HILO) {
+            float4 l = fl[Si[r]];
+            Sl[r] = make_float3(l.x, l.y, l.z);
+        } else {
+            Sl[r] = make_float3(0.f, 0.f, 0.f);
+        }
+        acc[r] = 0.0;
+    }
+    for (int jt = jt0; jt < jt1; ++jt) {
+        const int64_t j0 = (int64_t)jt * kTileJ;
+        __syncthreads();
+        load_tile3<HILO>(fx, fl, fn, s_x, s_l, s_n, j0);
+        __syncthreads();
+        float c[NI];
+#pragma unroll
+        for (int r = 0; r < NI; ++r) c[r] = 0.f;
+        if (tile_hits_diag(j0, ibase, kBlock * NI))
+            energy_tile32<true, NI, HILO>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, c);
+        else
+            energy_tile32<false, NI, HILO>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, c);
+#pragma unroll
+        for (int r = 0; r < NI; ++r) acc[r] += (double)c[r];
+    }
+#pragma unroll
+    for (int r = 0; r < NI; ++r) part[(int64_t)blockIdx.y * irows + Si[r]] = acc[r];
+}
+
+// ============================================================== energy + differential (FP32)
+//
+// Row ownership: face S collects every partial derivative with respect to its own
+// quantities, from the pairs (S,T) and (T,S) (both share d, r2 and 1/r2):
+//   dE/dX_S = a_S sum_T a_T [alpha (K/q) N_S + alpha (K'/q') N_T - beta (K + K') d / r2]
+//   dE/dN_S = a_S sum_T a_T alpha (K/q) d
+//   dE/da_S =     sum_T a_T (K + K')
+// with d = X_S - X_T, q = N_S.d, q' = N_T.d, K = K(S,T), K' = K(T,S).  The per-tile
+// accumulators c[0..10] are
+//   c0 = sum a_T K/q,  c1..3 = sum a_T (K'/q') N_T,  c4..6 = sum a_T (K+K')/r2 d,
+//   c7..9 = sum a_T (K/q) d,  c10 = sum a_T (K + K').
+constexpr int kGradAcc = 11;
+constexpr int kGradOut = 7;     // dE/dX (3), dE/dN (3), dE/da (1)
+
+template <bool DIAG, int NI, bool HILO, class Pow>
+__device__ __forceinline__ void grad_tile32(const float4* s_x, const float4* s_l, const float4* s_n,
+                                            int64_t j0, const float3 (&Sh)[NI],
+                                            const float3 (&Sl)[NI], const float3 (&Sn)[NI],
+                                            const int64_t (&Si)[NI], const Pow& pw,
+                                            float (&c)[NI][kGradAcc])
+{
+#pragma unroll 2
+    for (int jj = 0; jj < kTileJ; ++jj) {
+        const float4 tx = s_x[jj];
+        const float4 tn = s_n[jj];
+        float4 tl = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (HILO) tl = s_l[jj];
+        const float aT = tx.w;
+#pragma unroll
+        for (int r = 0; r < NI; ++r) {
+            float dx, dy, dz;
+            if (HILO) {
+                dx = (Sh[r].x - tx.x) + (Sl[r].x - tl.x);
+                dy = (Sh[r].y - tx.y) + (Sl[r].y - tl.y);
+                dz = (Sh[r].z - tx.z) + (Sl[r].z - tl.z);
+            } else {
+                dx = Sh[r].x - tx.x;
+                dy = Sh[r].y - tx.y;
+                dz = Sh[r].z - tx.z;
+            }
+            float r2 = dx * dx + dy * dy + dz * dz;
+            if (DIAG) r2 = (Si[r] == j0 + jj) ? 1.0f : r2;
+            const float inv = rcp_fast(r2);
+            const float q = Sn[r].x * dx + Sn[r].y * dy + Sn[r].z * dz;
+            const float qp = tn.x * dx + tn.y * dy + tn.z * dz;
+            float K, Kqr, Kp, Kpqr;
+            pw.KG(q, r2, inv, K, Kqr);
+            pw.KG(qp, r2, inv, Kp, Kpqr);
+            const float t = aT * inv;
+            const float aq = Kqr * t;
+            const float ap = Kpqr * t;
+            const float KK = K + Kp;
+            const float cc = KK * t;
+            c[r][0] += aq;
+            c[r][1] += ap * tn.x;
+            c[r][2] += ap * tn.y;
+            c[r][3] += ap * tn.z;
+            c[r][4] += cc * dx;
+            c[r][5] += cc * dy;
+            c[r][6] += cc * dz;
+            c[r][7] += aq * dx;
+            c[r][8] += aq * dy;
+            c[r][9] += aq * dz;
+            c[r][10] += KK * aT;
+        }
+    }
+}
+
+template <int NI, bool HILO, class Pow>
+__global__ __launch_bounds__(kBlock) void k_grad32(const float4* __restrict__ fx,
+                                                   const float4* __restrict__ fl,
+                                                   const float4* __restrict__ fn,
+                                                   const double4* __restrict__ dxa,
+                                                   const double4* __restrict__ dn,
+                                                   int tiles_per_split, int ntiles_j, double alpha,
+                                                   double beta, Pow pw, double* __restrict__ part,
+                                                   int64_t irows)
+{
+    __shared__ float4 s_x[kTileJ], s_l[HILO ? kTileJ : 1], s_n[kTileJ];
+    const int64_t ibase = (int64_t)blockIdx.x * (kBlock * NI);
+    const int jt0 = blockIdx.y * tiles_per_split;
+    const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
+    float3 Sh[NI], Sl[NI], Sn[NI];
+    int64_t Si[NI];
+    double acc[NI][kGradAcc];
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+        Si[r] = ibase + r * kBlock + threadIdx.x;
+        float4 x = fx[Si[r]], n = fn[Si[r]];
+        Sh[r] = make_float3(x.x, x.y, x.z);
+        Sn[r] = make_float3(n.x, n.y, n.z);
+        if (HILO) {
+            float4 l = fl[Si[r]];
+            Sl[r] = make_float3(l.x, l.y, l.z);
+        } else {
+            Sl[r] = make_float3(0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int m = 0; m < kGradAcc; ++m) acc[r][m] = 0.0;
+    }
+    for (int jt = jt0; jt < jt1; ++jt) {
+        const int64_t j0 = (int64_t)jt * kTileJ;
+        __syncthreads();
+        load_tile3<HILO>(fx, fl, fn, s_x, s_l, s_n, j0);
+        __syncthreads();
+        float c[NI][kGradAcc];
+#pragma unroll
+        for (int r = 0; r < NI; ++r)
+#pragma unroll
+            for (int m = 0; m < kGradAcc; ++m) c[r][m] = 0.f;
+        if (tile_hits_diag(j0, ibase, kBlock * NI))
+            grad_tile32<true, NI, HILO>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, c);
+        else
+            grad_tile32<false, NI, HILO>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, c);
+#pragma unroll
+        for (int r = 0; r < NI; ++r)
+#pragma unroll
+            for (int m = 0; m < kGradAcc; ++m) acc[r][m] += (double)c[r][m];
+    }
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+        const double aS = dxa[Si[r]].w;
+        const double4 N = dn[Si[r]];
+        const double* a = acc[r];
+        double out[kGradOut];
+        out[0] = aS * (alpha * (N.x * a[0] + a[1]) - beta * a[4]);
+        out[1] = aS * (alpha * (N.y * a[0] + a[2]) - beta * a[5]);
+        out[2] = aS * (alpha * (N.z * a[0] + a[3]) - beta * a[6]);
+        out[3] = aS * alpha * a[7];
+        out[4] = aS * alpha * a[8];
+        out[5] = aS * alpha * a[9];
+        out[6] = a[10];
+        double* dst = part + (int64_t)blockIdx.y * kGradOut * irows + Si[r];
+#pragma unroll
+        for (int m = 0; m < kGradOut; ++m) dst[m * irows] = out[m];
+    }
+}
+
+// ============================================================== fractional apply (FP32)
+//
+// z(S) = sum_{T != S} |X_S - X_T|^-(2 sigma + 2) a_T (ubar_S - ubar_T)  for KC columns,
+// the row sum of [diag(diag(a)^-1 H a) - H] U u divided by a_S (Sec. 5.1.1, App. A); the
+// remaining factors 2 U^T diag(a) are applied per vertex afterwards.  Differences of the
+// face averages are taken per pair, so no large cancelling sums are formed.
+template <int KC>
+struct KPad { static constexpr int value = (KC + 3) / 4 * 4; };
+
+template <bool DIAG, int NI, int KC, bool HILO>
+__device__ __forceinline__ void frac_tile32(const float4* s_x, const float4* s_l, const float* s_u,
+                                            int64_t j0, const float3 (&Sh)[NI],
+                                            const float3 (&Sl)[NI], const float (&Su)[NI][KC],
+                                            const int64_t (&Si)[NI], float expo,
+                                            float (&c)[NI][KC])
+{
+    constexpr int KP = KPad<KC>::value;
+#pragma unroll 2
+    for (int jj = 0; jj < kTileJ; ++jj) {
+        const float4 tx = s_x[jj];
+        float4 tl = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (HILO) tl = s_l[jj];
+        float tu[KP];
+#pragma unroll
+        for (int q = 0; q < KP / 4; ++q) {
+            float4 v = reinterpret_cast<const float4*>(s_u + jj * KP)[q];
+            tu[4 * q] = v.x; tu[4 * q + 1] = v.y; tu[4 * q + 2] = v.z; tu[4 * q + 3] = v.w;
+        }
+#pragma unroll
+        for (int r = 0; r < NI; ++r) {
+            float dx, dy, dz;
+            if (HILO) {
+                dx = (Sh[r].x - tx.x) + (Sl[r].x - tl.x);
+                dy = (Sh[r].y - tx.y) + (Sl[r].y - tl.y);
+                dz = (Sh[r].z - tx.z) + (Sl[r].z - tl.z);
+            } else {
+                dx = Sh[r].x - tx.x;
+                dy = Sh[r].y - tx.y;
+                dz = Sh[r].z - tx.z;
+            }
+            float r2 = dx * dx + dy * dy + dz * dz;
+            if (DIAG) r2 = (Si[r] == j0 + jj) ? 1.0f : r2;
+            const float w = exp2_fast(expo * log2_fast(r2)) * tx.w;
+#pragma unroll
+            for (int cc = 0; cc < KC; ++cc) c[r][cc] += w * (Su[r][cc] - tu[cc]);
+        }
+    }
+}
+
+template <int NI, int KC, bool HILO>
+__global__ __launch_bounds__(kBlock) void k_frac32(const float4* __restrict__ fx,
+                                                   const float4* __restrict__ fl,
+                                                   const float* __restrict__ ub,
+                                                   int tiles_per_split, int ntiles_j, float expo,
+                                                   double* __restrict__ part, int64_t irows)
+{
+    constexpr int KP = KPad<KC>::value;
+    __shared__ float4 s_x[kTileJ], s_l[HILO ? kTileJ : 1];
+    __shared__ __align__(16) float s_u[kTileJ * KP];
+    const int64_t ibase = (int64_t)blockIdx.x * (kBlock * NI);
+    const int jt0 = blockIdx.y * tiles_per_split;
+    const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
+    float3 Sh[NI], Sl[NI];
+    float Su[NI][KC];
+    int64_t Si[NI];
+    double acc[NI][KC];
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+        Si[r] = ibase + r * kBlock + threadIdx.x;
+        float4 x = fx[Si[r]];
+        Sh[r] = make_float3(x.x, x.y, x.z);
+        if (HILO) {
+            float4 l = fl[Si[r]];
+            Sl[r] = make_float3(l.x, l.y, l.z);
+        } else {
+            Sl[r] = make_float3(0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int cc = 0; cc < KC; ++cc) {
+            Su[r][cc] = ub[Si[r] * KP + cc];
+            acc[r][cc] = 0.0;
+        }
+    }
+    for (int jt = jt0; jt < jt1; ++jt) {
+        const int64_t j0 = (int64_t)jt * kTileJ;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kTileJ; e += kBlock) {
+            s_x[e] = fx[j0 + e];
+            if (HILO) s_l[e] = fl[j0 + e];
+        }
+        for (int e = threadIdx.x; e < kTileJ * KP / 4; e += kBlock)
+            reinterpret_cast<float4*>(s_u)[e] = reinterpret_cast<const float4*>(ub + j0 * KP)[e];
+        __syncthreads();
+        float c[NI][KC];
+#pragma unroll
+        for (int r = 0; r < NI; ++r)
+#pragma unroll
+            for (int cc = 0; cc < KC; ++cc) c[r][cc] = 0.f;
+        if (tile_hits_diag(j0, ibase, kBlock * NI))
+            frac_tile32<true, NI, KC, HILO>(s_x, s_l, s_u, j0, Sh, Sl, Su, Si, expo, c);
+        else
+            frac_tile32<false, NI, KC, HILO>(s_x, s_l, s_u, j0, Sh, Sl, Su, Si, expo, c);
+#pragma unroll
+        for (int r = 0; r < NI; ++r)
+#pragma unroll
+            for (int cc = 0; cc < KC; ++cc) acc[r][cc] += (double)c[r][cc];
+    }
+#pragma unroll
+    for (int r = 0; r < NI; ++r)
+#pragma unroll
+        for (int cc = 0; cc < KC; ++cc)
+            part[((int64_t)blockIdx.y * KC + cc) * irows + Si[r]] = acc[r][cc];
+}
+
+// ============================================================== FP64 variants
+//
+// Same structure with double pair terms and no per-tile FP32 stage.
+
+__device__ __forceinline__ void load_tile64(const double4* __restrict__ dxa,
+                                            const double4* __restrict__ dn, double4* s_x,
+                                            double4* s_n, int64_t j0, bool with_n)
+{
+    for (int e = threadIdx.x; e < kTileJ; e += kBlock) {
+        s_x[e] = dxa[j0 + e];
+        if (with_n) s_n[e] = dn[j0 + e];
+    }
+}
+
+template <bool DIAG, class Pow>
+__device__ __forceinline__ void energy_tile64(const double4* s_x, int64_t j0, double3 S, double3 N,
+                                              int64_t Si, const Pow& pw, double& c)
+{
+#pragma unroll 2
+    for (int jj = 0; jj < kTileJ; ++jj) {
+        const double4 t = s_x[jj];
+        double dx = S.x - t.x, dy = S.y - t.y, dz = S.z - t.z;
+        double r2 = dx * dx + dy * dy + dz * dz;
+        if (DIAG) r2 = (Si == j0 + jj) ? 1.0 : r2;
+        const double inv = rcp_fast(r2);
+        const double q = N.x * dx + N.y * dy + N.z * dz;
+        c += pw.K(q, r2, inv) * t.w;
+    }
+}
+
+template <class Pow>
+__global__ __launch_bounds__(kBlock) void k_energy64(const double4* __restrict__ dxa,
+                                                     const double4* __restrict__ dn,
+                                                     int tiles_per_split, int ntiles_j, Pow pw,
+                                                     double* __restrict__ part, int64_t irows)
+{
+    __shared__ double4 s_x[kTileJ];
+    const int64_t ibase = (int64_t)blockIdx.x * kBlock;
+    const int jt0 = blockIdx.y * tiles_per_split;
+    const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
+    const int64_t Si = ibase + threadIdx.x;
+    const double4 x = dxa[Si], n = dn[Si];
+    const double3 S = make_double3(x.x, x.y, x.z), N = make_double3(n.x, n.y, n.z);
+    double acc = 0.0;
+    for (int jt = jt0; jt < jt1; ++jt) {
+        const int64_t j0 = (int64_t)jt * kTileJ;
+        __syncthreads();
+        load_tile64(dxa, dn, s_x, nullptr, j0, false);
+        __syncthreads();
+        if (tile_hits_diag(j0, ibase, kBlock)) energy_tile64<true>(s_x, j0, S, N, Si, pw, acc);
+        else energy_tile64<false>(s_x, j0, S, N, Si, pw, acc);
+    }
+    part[(int64_t)blockIdx.y * irows + Si] = acc;
+}
+
+template <bool DIAG, class Pow>
+__device__ __forceinline__ void grad_tile64(const double4* s_x, const double4* s_n, int64_t j0,
+                                            double3 S, double3 N, int64_t Si, const Pow& pw,
+                                            double (&c)[kGradAcc])
+{
+#pragma unroll 2
+    for (int jj = 0; jj < kTileJ; ++jj) {
+        const double4 tx = s_x[jj];
+        const double4 tn = s_n[jj];
+        const double aT = tx.w;
+        double dx = S.x - tx.x, dy = S.y - tx.y, dz = S.z - tx.z;
+        double r2 = dx * dx + dy * dy + dz * dz;
+        if (DIAG) r2 = (Si == j0 + jj) ? 1.0 : r2;
+        const double inv = rcp_fast(r2);
+        const double q = N.x * dx + N.y * dy + N.z * dz;
+        const double qp = tn.x * dx + tn.y * dy + tn.z * dz;
+        double K, Kqr, Kp, Kpqr;
+        pw.KG(q, r2, inv, K, Kqr);
+        pw.KG(qp, r2, inv, Kp, Kpqr);
+        const double t = aT * inv;
+        const double aq = Kqr * t;
+        const double ap = Kpqr * t;
+        const double KK = K + Kp;
+        const double cc = KK * t;
+        c[0] += aq;
+        c[1] += ap * tn.x;
+        c[2] += ap * tn.y;
+        c[3] += ap * tn.z;
+        c[4] += cc * dx;
+        c[5] += cc * dy;
+        c[6] += cc * dz;
+        c[7] += aq * dx;
+        c[8] += aq * dy;
+        c[9] += aq * dz;
+        c[10] += KK * aT;
+    }
+}
+
+template <class Pow>
+__global__ __launch_bounds__(kBlock) void k_grad64(const double4* __restrict__ dxa,
+                                                   const double4* __restrict__ dn,
+                                                   int tiles_per_split, int ntiles_j, double alpha,
+                                                   double beta, Pow pw, double* __restrict__ part,
+                                                   int64_t irows)
+{
+    __shared__ double4 s_x[kTileJ], s_n[kTileJ];
+    const int64_t ibase = (int64_t)blockIdx.x * kBlock;
+    const int jt0 = blockIdx.y * tiles_per_split;
+    const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
+    const int64_t Si = ibase + threadIdx.x;
+    const double4 x = dxa[Si], n = dn[Si];
+    const double3 S = make_double3(x.x, x.y, x.z), N = make_double3(n.x, n.y, n.z);
+    double a[kGradAcc];
+#pragma unroll
+    for (int m = 0; m < kGradAcc; ++m) a[m] = 0.0;
+    for (int jt = jt0; jt < jt1; ++jt) {
+        const int64_t j0 = (int64_t)jt * kTileJ;
+        __syncthreads();
+        load_tile64(dxa, dn, s_x, s_n, j0, true);
+        __syncthreads();
+        if (tile_hits_diag(j0, ibase, kBlock)) grad_tile64<true>(s_x, s_n, j0, S, N, Si, pw, a);
+        else grad_tile64<false>(s_x, s_n, j0, S, N, Si, pw, a);
+    }
+    const double aS = x.w;
+    double out[kGradOut];
+    out[0] = aS * (alpha * (N.x * a[0] + a[1]) - beta * a[4]);
+    out[1] = aS * (alpha * (N.y * a[0] + a[2]) - beta * a[5]);
+    out[2] = aS * (alpha * (N.z * a[0] + a[3]) - beta * a[6]);
+    out[3] = aS * alpha * a[7];
+    out[4] = aS * alpha * a[8];
+    out[5] = aS * alpha * a[9];
+    out[6] = a[10];
+    double* dst = part + (int64_t)blockIdx.y * kGradOut * irows + Si;
+#pragma unroll
+    for (int m = 0; m < kGradOut; ++m) dst[m * irows] = out[m];
+}
+
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_frac64(const double4* __restrict__ dxa,
+                                                   const double* __restrict__ ub,
+                                                   int tiles_per_split, int ntiles_j, double expo,
+                                                   double* __restrict__ part, int64_t irows)
+{
+    constexpr int KP = KPad<KC>::value;
+    __shared__ double4 s_x[kTileJ];
+    __shared__ double s_u[kTileJ * KP];
+    const int64_t ibase = (int64_t)blockIdx.x * kBlock;
+    const int jt0 = blockIdx.y * tiles_per_split;
+    const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
+    const int64_t Si = ibase + threadIdx.x;
+    const double4 x = dxa[Si];
+    double Su[KC], acc[KC];
+#pragma unroll
+    for (int cc = 0; cc < KC; ++cc) {
+        Su[cc] = ub[Si * KP + cc];
+        acc[cc] = 0.0;
+    }
+    for (int jt = jt0; jt < jt1; ++jt) {
+        const int64_t j0 = (int64_t)jt * kTileJ;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kTileJ; e += kBlock) s_x[e] = dxa[j0 + e];
+        for (int e = threadIdx.x; e < kTileJ * KP; e += kBlock) s_u[e] = ub[j0 * KP + e];
+        __syncthreads();
+        const bool diag = tile_hits_diag(j0, ibase, kBlock);
+        for (int jj = 0; jj < kTileJ; ++jj) {
+            const double4 t = s_x[jj];
+            double dx = x.x - t.x, dy = x.y - t.y, dz = x.z - t.z;
+            double r2 = dx * dx + dy * dy + dz * dz;
+            if (diag && Si == j0 + jj) continue;
+            const double w = pow(r2, expo) * t.w;
+#pragma unroll
+            for (int cc = 0; cc < KC; ++cc) acc[cc] += w * (Su[cc] - s_u[jj * KP + cc]);
+        }
+    }
+#pragma unroll
+    for (int cc = 0; cc < KC; ++cc) part[((int64_t)blockIdx.y * KC + cc) * irows + Si] = acc[cc];
+}
+
+// ============================================================== split reduction
+
+__global__ void k_reduce_splits(const double* __restrict__ part, int n_split, int nacc,
+                                int64_t irows, int64_t n, double* __restrict__ out,
+                                int64_t out_stride)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * nacc) return;
+    const int acc = (int)(t / n);
+    const int64_t i = t - (int64_t)acc * n;
+    double s = 0.0;
+    for (int sp = 0; sp < n_split; ++sp) s += part[((int64_t)sp * nacc + acc) * irows + i];
+    out[(int64_t)acc * out_stride + i] = s;
+}
+
+hipError_t launch_reduce_splits(const double* part, int n_split, int nacc, int64_t irows,
+                                int64_t n, double* out, int64_t out_stride, hipStream_t s)
+{
+    const int64_t total = n * nacc;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_reduce_splits, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
+                       part, n_split, nacc, irows, n, out, out_stride);
+    return hipGetLastError();
+}
+
+// ============================================================== planning and launch
+
+int64_t face_capacity(int64_t nF, int ni_max)
+{
+    const int64_t g = (int64_t)kBlock * ni_max;
+    int64_t cap = (nF + g - 1) / g * g;
+    return std::max<int64_t>(cap, kTileJ);
+}
+
+PairPlan plan_pairs(int64_t nF, int64_t cap, int ni, int occupancy_per_cu)
+{
+    PairPlan pl;
+    pl.ni = ni;
+    const int64_t ispan = (int64_t)kBlock * ni;
+    pl.n_itiles = (int)((nF + ispan - 1) / ispan);
+    pl.irows = (int64_t)pl.n_itiles * ispan;
+    pl.ntiles_j = (int)((nF + kTileJ - 1) / kTileJ);
+    (void)cap;
+    const int64_t slots = std::max<int64_t>(1, (int64_t)device_info().num_cu * std::max(1, occupancy_per_cu));
+    double best = 1e300;
+    int best_tps = pl.ntiles_j;
+    for (int tps = 1; tps <= pl.ntiles_j; ++tps) {
+        const int64_t ns = (pl.ntiles_j + tps - 1) / tps;
+        if (tps > 1 && (pl.ntiles_j + tps - 2) / (tps - 1) == ns) continue;  // same split count
+        const int64_t wg = (int64_t)pl.n_itiles * ns;
+        const int64_t waves = (wg + slots - 1) / slots;
+        // makespan in tiles, plus a small charge per split for the partial sums
+        const double cost = (double)waves * tps + 0.05 * (double)ns;
+        if (cost < best) {
+            best = cost;
+            best_tps = tps;
+        }
+    }
+    pl.tiles_per_split = best_tps;
+    pl.n_split = (pl.ntiles_j + best_tps - 1) / best_tps;
+    return pl;
+}
+
+namespace {
+
+// Occupancy (workgroups per CU) of a kernel, queried once per function.
+int occupancy_of(const void* fn)
+{
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(fn);
+    if (it != cache.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+    cache[fn] = nb;
+    return nb;
+}
+
+bool is_p6(double alpha, double beta) { return alpha == 6.0 && beta == 12.0; }
+
+PowGen make_gen(double alpha, double beta)
+{
+    PowGen g;
+    g.am1 = (float)(alpha - 1.0);
+    g.hb = (float)(beta * 0.5);
+    g.am1d = alpha - 1.0;
+    g.hbd = beta * 0.5;
+    return g;
+}
+
+constexpr int kNiEnergy32 = 4, kNiGrad32 = 2, kNiFrac32 = 2;
+
+const void* energy_fn(int precision, bool p6)
+{
+    if (precision == TP_PREC_FP64)
+        return p6 ? (const void*)k_energy64<PowP6> : (const void*)k_energy64<PowGen>;
+    const bool hilo = precision == TP_PREC_FP32_HILO;
+    if (p6) return hilo ? (const void*)k_energy32<kNiEnergy32, true, PowP6>
+                        : (const void*)k_energy32<kNiEnergy32, false, PowP6>;
+    return hilo ? (const void*)k_energy32<kNiEnergy32, true, PowGen>
+                : (const void*)k_energy32<kNiEnergy32, false, PowGen>;
+}
+
+const void* grad_fn(int precision, bool p6)
+{
+    if (precision == TP_PREC_FP64)
+        return p6 ? (const void*)k_grad64<PowP6> : (const void*)k_grad64<PowGen>;
+    const bool hilo = precision == TP_PREC_FP32_HILO;
+    if (p6) return hilo ? (const void*)k_grad32<kNiGrad32, true, PowP6>
+                        : (const void*)k_grad32<kNiGrad32, false, PowP6>;
+    return hilo ? (const void*)k_grad32<kNiGrad32, true, PowGen>
+                : (const void*)k_grad32<kNiGrad32, false, PowGen>;
+}
+
+template <int KC>
+const void* frac_fn_k(int precision)
+{
+    if (precision == TP_PREC_FP64) return (const void*)k_frac64<KC>;
+    if (precision == TP_PREC_FP32_HILO) return (const void*)k_frac32<kNiFrac32, KC, true>;
+    return (const void*)k_frac32<kNiFrac32, KC, false>;
+}
+
+const void* frac_fn(int precision, int k)
+{
+    switch (k) {
+    case 1: return frac_fn_k<1>(precision);
+    case 2: return frac_fn_k<2>(precision);
+    case 3: return frac_fn_k<3>(precision);
+    case 4: return frac_fn_k<4>(precision);
+    case 5: return frac_fn_k<5>(precision);
+    case 6: return frac_fn_k<6>(precision);
+    case 7: return frac_fn_k<7>(precision);
+    case 8: return frac_fn_k<8>(precision);
+    case 9: return frac_fn_k<9>(precision);
+    default: return nullptr;
+    }
+}
+
+int ni_of(int kind, int precision)
+{
+    if (precision == TP_PREC_FP64) return 1;
+    return kind == kKindEnergy ? kNiEnergy32 : (kind == kKindGrad ? kNiGrad32 : kNiFrac32);
+}
+
+}  // namespace
+
+PairPlan plan_for(int kind, int precision, int k, int64_t nF, int64_t cap)
+{
+    const void* fn = kind == kKindEnergy ? energy_fn(precision, true)
+                   : kind == kKindGrad   ? grad_fn(precision, true)
+                                         : frac_fn(precision, std::max(1, std::min(k, kMaxGroupCols)));
+    return plan_pairs(nF, cap, ni_of(kind, precision), occupancy_of(fn));
+}
+
+hipError_t launch_pairs_energy(const FaceData& fd, const PairPlan& pl, int precision,
+                               double alpha, double beta, double* part, hipStream_t s)
+{
+    const dim3 grid(pl.n_itiles, pl.n_split), block(kBlock);
+    const bool p6 = is_p6(alpha, beta);
+    const PowGen g = make_gen(alpha, beta);
+    if (precision == TP_PREC_FP64) {
+        if (p6) hipLaunchKernelGGL(k_energy64<PowP6>, grid, block, 0, s, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, PowP6{}, part, pl.irows);
+        else hipLaunchKernelGGL(k_energy64<PowGen>, grid, block, 0, s, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, g, part, pl.irows);
+    } else if (precision == TP_PREC_FP32_HILO) {
+        if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, PowP6>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, pl.tiles_per_split, pl.ntiles_j, PowP6{}, part, pl.irows);
+        else hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, PowGen>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, pl.tiles_per_split, pl.ntiles_j, g, part, pl.irows);
+    } else {
+        if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, PowP6>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, pl.tiles_per_split, pl.ntiles_j, PowP6{}, part, pl.irows);
+        else hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, PowGen>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, pl.tiles_per_split, pl.ntiles_j, g, part, pl.irows);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_pairs_grad(const FaceData& fd, const PairPlan& pl, int precision,
+                             double alpha, double beta, double* part, hipStream_t s)
+{
+    const dim3 grid(pl.n_itiles, pl.n_split), block(kBlock);
+    const bool p6 = is_p6(alpha, beta);
+    const PowGen g = make_gen(alpha, beta);
+    if (precision == TP_PREC_FP64) {
+        if (p6) hipLaunchKernelGGL(k_grad64<PowP6>, grid, block, 0, s, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, PowP6{}, part, pl.irows);
+        else hipLaunchKernelGGL(k_grad64<PowGen>, grid, block, 0, s, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, g, part, pl.irows);
+    } else if (precision == TP_PREC_FP32_HILO) {
+        if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, true, PowP6>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, PowP6{}, part, pl.irows);
+        else hipLaunchKernelGGL((k_grad32<kNiGrad32, true, PowGen>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, g, part, pl.irows);
+    } else {
+        if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, false, PowP6>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, PowP6{}, part, pl.irows);
+        else hipLaunchKernelGGL((k_grad32<kNiGrad32, false, PowGen>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, g, part, pl.irows);
+    }
+    return hipGetLastError();
+}
+
+template <int KC>
+static void launch_frac_k(const FaceData& fd, const PairPlan& pl, int precision, double expo,
+                          const void* ub, double* part, hipStream_t s)
+{
+    const dim3 grid(pl.n_itiles, pl.n_split), block(kBlock);
+    if (precision == TP_PREC_FP64)
+        hipLaunchKernelGGL(k_frac64<KC>, grid, block, 0, s, fd.dx, (const double*)ub, pl.tiles_per_split, pl.ntiles_j, expo, part, pl.irows);
+    else if (precision == TP_PREC_FP32_HILO)
+        hipLaunchKernelGGL((k_frac32<kNiFrac32, KC, true>), grid, block, 0, s, fd.fx, fd.fl, (const float*)ub, pl.tiles_per_split, pl.ntiles_j, (float)expo, part, pl.irows);
+    else
+        hipLaunchKernelGGL((k_frac32<kNiFrac32, KC, false>), grid, block, 0, s, fd.fx, fd.fl, (const float*)ub, pl.tiles_per_split, pl.ntiles_j, (float)expo, part, pl.irows);
+}
+
+hipError_t launch_pairs_frac(const FaceData& fd, const PairPlan& pl, int precision,
+                             double sigma, const void* ub, int k, int kp, double* part,
+                             hipStream_t s)
+{
+    (void)kp;
+    const double expo = -(2.0 * sigma + 2.0) * 0.5;   // |d|^-(2 sigma + 2) = r2^expo
+    switch (k) {
+    case 1: launch_frac_k<1>(fd, pl, precision, expo, ub, part, s); break;
+    case 2: launch_frac_k<2>(fd, pl, precision, expo, ub, part, s); break;
+    case 3: launch_frac_k<3>(fd, pl, precision, expo, ub, part, s); break;
+    case 4: launch_frac_k<4>(fd, pl, precision, expo, ub, part, s); break;
+    case 5: launch_frac_k<5>(fd, pl, precision, expo, ub, part, s); break;
+    case 6: launch_frac_k<6>(fd, pl, precision, expo, ub, part, s); break;
+    case 7: launch_frac_k<7>(fd, pl, precision, expo, ub, part, s); break;
+    case 8: launch_frac_k<8>(fd, pl, precision, expo, ub, part, s); break;
+    case 9: launch_frac_k<9>(fd, pl, precision, expo, ub, part, s); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace tp

@@ -1,0 +1,319 @@
+"""Thin ctypes binding of libtpsurf (include/tpsurf.h).
+
+Argument marshalling only: every step runs in the HIP library.  Tensors must live on a
+HIP device (torch "cuda" device), be contiguous and have the documented dtype; results
+are returned as new device tensors.  There is no CPU fallback: if the library is not
+built, loading fails with an error.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libtpsurf.so")
+
+TP_OK = 0
+STATUS_NAMES = {
+    0: "TP_OK", 1: "TP_E_INVALID_ARGUMENT", 2: "TP_E_DEGENERATE_FACE", 3: "TP_E_BAD_INDEX",
+    4: "TP_E_NONFINITE", 5: "TP_E_NOT_CONVERGED", 6: "TP_E_OUT_OF_MEMORY",
+    7: "TP_E_SINGULAR_CONSTRAINTS", 8: "TP_E_DEVICE",
+}
+PREC_FP32_HILO, PREC_FP32, PREC_FP64 = 0, 1, 2
+KIND_ENERGY, KIND_GRAD, KIND_FRAC = 0, 1, 2
+
+# Every symbol the C-ABI exports (the header declares exactly these).
+EXPORTED = [
+    "tp_params_default", "tp_energy", "tp_gradient", "tp_energy_faces", "tp_fractional_apply",
+    "tp_precond_apply", "tp_problem_create", "tp_problem_destroy", "tp_problem_set_vertices",
+    "tp_problem_get_vertices", "tp_problem_energy", "tp_problem_gradient",
+    "tp_problem_fractional_apply", "tp_problem_precond_apply", "tp_step_opts_default",
+    "tp_precond_step", "tp_last_error", "tp_profile_enable", "tp_profile_reset", "tp_profile_get",
+]
+
+
+class TpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("precision", ctypes.c_int), ("cg_rtol", ctypes.c_double), ("cg_maxiter", ctypes.c_int)]
+
+
+class SolveReport(ctypes.Structure):
+    _fields_ = [("cg_iters", ctypes.c_int * 2), ("cg_relres", ctypes.c_double * 2),
+                ("t_ms", ctypes.c_double * 4)]
+
+
+class StepOpts(ctypes.Structure):
+    _fields_ = [("tau0", ctypes.c_double), ("line_search", ctypes.c_int), ("armijo_c", ctypes.c_double),
+                ("shrink", ctypes.c_double), ("max_backtracks", ctypes.c_int),
+                ("constrain_area", ctypes.c_int), ("constrain_volume", ctypes.c_int),
+                ("area_target", ctypes.c_double), ("volume_target", ctypes.c_double)]
+
+
+class StepReport(ctypes.Structure):
+    _fields_ = [("E", ctypes.c_double), ("E_new", ctypes.c_double), ("grad_norm", ctypes.c_double),
+                ("slope", ctypes.c_double), ("tau", ctypes.c_double), ("backtracks", ctypes.c_int),
+                ("n_constraints", ctypes.c_int), ("cg_iters", ctypes.c_int * 2),
+                ("cg_relres", ctypes.c_double * 2), ("phi_before", ctypes.c_double * 2),
+                ("phi_trial", ctypes.c_double * 2), ("phi_after", ctypes.c_double * 2),
+                ("t_ms", ctypes.c_double * 8)]
+
+    def as_dict(self) -> dict:
+        out = {}
+        for name, _ in self._fields_:
+            v = getattr(self, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+
+class KernelStats(ctypes.Structure):
+    _fields_ = [("ms_total", ctypes.c_double), ("pairs_total", ctypes.c_double),
+                ("cols_total", ctypes.c_double), ("launches", ctypes.c_int64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libtpsurf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_2107_01664_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, d, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+    P = ctypes.POINTER
+    sig = {
+        "tp_params_default": [P(Params)],
+        "tp_energy": [vp, i64, vp, i64, P(Params), P(d), vp],
+        "tp_gradient": [vp, i64, vp, i64, P(Params), P(d), vp, vp],
+        "tp_energy_faces": [vp, vp, vp, i64, P(Params), P(d), vp],
+        "tp_fractional_apply": [vp, i64, vp, i64, P(Params), vp, i32, vp, vp],
+        "tp_precond_apply": [vp, i64, vp, i64, P(Params), vp, i32, vp, P(SolveReport), vp],
+        "tp_problem_create": [vp, i64, vp, i64, P(Params), vp, P(vp)],
+        "tp_problem_set_vertices": [vp, vp],
+        "tp_problem_get_vertices": [vp, vp],
+        "tp_problem_energy": [vp, P(d)],
+        "tp_problem_gradient": [vp, P(d), vp],
+        "tp_problem_fractional_apply": [vp, vp, i32, vp],
+        "tp_problem_precond_apply": [vp, vp, i32, vp, P(SolveReport)],
+        "tp_step_opts_default": [P(StepOpts)],
+        "tp_precond_step": [vp, P(StepOpts), P(StepReport), vp],
+        "tp_profile_enable": [i32],
+        "tp_profile_reset": [],
+        "tp_profile_get": [i32, P(KernelStats)],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.tp_problem_destroy.argtypes = [vp]
+    L.tp_problem_destroy.restype = None
+    L.tp_last_error.argtypes = []
+    L.tp_last_error.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(status: int, allow=()):
+    if status != TP_OK and status not in allow:
+        raise TpError(status, (lib().tp_last_error() or b"").decode())
+    return status
+
+
+def default_params(**kw) -> Params:
+    p = Params()
+    _check(lib().tp_params_default(ctypes.byref(p)))
+    for k, v in kw.items():
+        if not hasattr(p, k):
+            raise KeyError(k)
+        setattr(p, k, v)
+    return p
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype, name: str, cols: Optional[int] = None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    if cols is not None and (t.dim() != 2 or t.shape[1] != cols):
+        raise ValueError(f"{name} must have shape (n, {cols})")
+    return t.contiguous()
+
+
+def _mesh(V, F):
+    return _dev(V, torch.float64, "V", 3), _dev(F, torch.int32, "F", 3)
+
+
+def tp_energy(V, F, params: Optional[Params] = None) -> float:
+    V, F = _mesh(V, F)
+    E = ctypes.c_double()
+    _check(lib().tp_energy(V.data_ptr(), V.shape[0], F.data_ptr(), F.shape[0],
+                           ctypes.byref(params or default_params()), ctypes.byref(E), _stream()))
+    return E.value
+
+
+def tp_gradient(V, F, params: Optional[Params] = None):
+    V, F = _mesh(V, F)
+    dE = torch.empty_like(V)
+    E = ctypes.c_double()
+    _check(lib().tp_gradient(V.data_ptr(), V.shape[0], F.data_ptr(), F.shape[0],
+                             ctypes.byref(params or default_params()), ctypes.byref(E),
+                             dE.data_ptr(), _stream()))
+    return E.value, dE
+
+
+def tp_energy_faces(X, N, a, params: Optional[Params] = None) -> float:
+    X = _dev(X, torch.float64, "X", 3)
+    N = _dev(N, torch.float64, "N", 3)
+    a = _dev(a, torch.float64, "a")
+    E = ctypes.c_double()
+    _check(lib().tp_energy_faces(X.data_ptr(), N.data_ptr(), a.data_ptr(), a.shape[0],
+                                 ctypes.byref(params or default_params()), ctypes.byref(E), _stream()))
+    return E.value
+
+
+def _cols(u, nV, name):
+    u = _dev(u, torch.float64, name)
+    if u.dim() == 1:
+        u = u.reshape(-1, 1)
+    if u.shape[0] != nV:
+        raise ValueError(f"{name} must have {nV} rows")
+    return u.contiguous()
+
+
+def tp_fractional_apply(V, F, u, params: Optional[Params] = None):
+    V, F = _mesh(V, F)
+    squeeze = u.dim() == 1
+    u = _cols(u, V.shape[0], "u")
+    Lu = torch.empty_like(u)
+    _check(lib().tp_fractional_apply(V.data_ptr(), V.shape[0], F.data_ptr(), F.shape[0],
+                                     ctypes.byref(params or default_params()), u.data_ptr(),
+                                     u.shape[1], Lu.data_ptr(), _stream()))
+    return Lu[:, 0] if squeeze else Lu
+
+
+def tp_precond_apply(V, F, b, params: Optional[Params] = None):
+    V, F = _mesh(V, F)
+    squeeze = b.dim() == 1
+    b = _cols(b, V.shape[0], "b")
+    x = torch.empty_like(b)
+    rep = SolveReport()
+    _check(lib().tp_precond_apply(V.data_ptr(), V.shape[0], F.data_ptr(), F.shape[0],
+                                  ctypes.byref(params or default_params()), b.data_ptr(), b.shape[1],
+                                  x.data_ptr(), ctypes.byref(rep), _stream()))
+    return (x[:, 0] if squeeze else x), rep
+
+
+def step_opts(**kw) -> StepOpts:
+    o = StepOpts()
+    _check(lib().tp_step_opts_default(ctypes.byref(o)))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Problem:
+    """Resident problem (tp_problem_*): topology, vertices and work buffers stay on the device."""
+
+    def __init__(self, V, F, params: Optional[Params] = None):
+        V, F = _mesh(V, F)
+        self.nV, self.nF = V.shape[0], F.shape[0]
+        self.device = V.device
+        h = ctypes.c_void_p()
+        _check(lib().tp_problem_create(V.data_ptr(), self.nV, F.data_ptr(), self.nF,
+                                       ctypes.byref(params or default_params()), _stream(),
+                                       ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().tp_problem_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_vertices(self, V):
+        V = _dev(V, torch.float64, "V", 3)
+        _check(lib().tp_problem_set_vertices(self._h, V.data_ptr()))
+
+    def vertices(self):
+        out = torch.empty((self.nV, 3), dtype=torch.float64, device=self.device)
+        _check(lib().tp_problem_get_vertices(self._h, out.data_ptr()))
+        return out
+
+    def energy(self) -> float:
+        E = ctypes.c_double()
+        _check(lib().tp_problem_energy(self._h, ctypes.byref(E)))
+        return E.value
+
+    def gradient(self, out=None):
+        dE = out if out is not None else torch.empty((self.nV, 3), dtype=torch.float64, device=self.device)
+        E = ctypes.c_double()
+        _check(lib().tp_problem_gradient(self._h, ctypes.byref(E), dE.data_ptr()))
+        return E.value, dE
+
+    def fractional_apply(self, u, out=None):
+        squeeze = u.dim() == 1
+        u = _cols(u, self.nV, "u")
+        Lu = out if out is not None else torch.empty_like(u)
+        _check(lib().tp_problem_fractional_apply(self._h, u.data_ptr(), u.shape[1], Lu.data_ptr()))
+        return Lu[:, 0] if squeeze else Lu
+
+    def precond_apply(self, b, out=None, allow_not_converged=False):
+        squeeze = b.dim() == 1
+        b = _cols(b, self.nV, "b")
+        x = out if out is not None else torch.empty_like(b)
+        rep = SolveReport()
+        allow = (5,) if allow_not_converged else ()
+        _check(lib().tp_problem_precond_apply(self._h, b.data_ptr(), b.shape[1], x.data_ptr(),
+                                              ctypes.byref(rep)), allow)
+        return (x[:, 0] if squeeze else x), rep
+
+    def step(self, opts: Optional[StepOpts] = None, direction=None):
+        rep = StepReport()
+        ptr = direction.data_ptr() if direction is not None else None
+        _check(lib().tp_precond_step(self._h, ctypes.byref(opts or step_opts()), ctypes.byref(rep), ptr))
+        return rep
+
+
+def profile_enable(on: bool = True):
+    _check(lib().tp_profile_enable(1 if on else 0))
+
+
+def profile_reset():
+    _check(lib().tp_profile_reset())
+
+
+def profile_get(kind: int) -> dict:
+    st = KernelStats()
+    _check(lib().tp_profile_get(kind, ctypes.byref(st)))
+    return {"ms_total": st.ms_total, "pairs_total": st.pairs_total, "cols_total": st.cols_total,
+            "launches": int(st.launches)}
