@@ -1,0 +1,211 @@
+"""Benchmark of the tangent-point hot path on one MI355X.
+
+One step on the 40,000-face noisy torus (R = 1, r = 0.3, 200 x 100 grid, vertex noise
+0.002 r, seed 0), with inputs resident in HBM:
+  1. E and dE (all pairs, FP32 pair terms, FP64 accumulation),
+  2. L^sigma u for u ~ N(0,1) in R^{V x 3} (all pairs),
+  3. A~^{-1} dE = C^-1 L^sigma C^-1 dE: two FP64 CG Poisson solves (1e-10) around one more
+     all-pairs fractional apply on 3 columns.
+value = ordered face-pair interactions per second over the whole step (3 F (F - 1) per step).
+
+Prints ONE JSON line (rank 0).  `--gpus N` with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic work per ordered face pair (FMA = 2 FLOP, other arithmetic and
+# transcendental = 1), counted from the formulas evaluated once per pair:
+#   energy + differential: 57, fractional apply with k columns: 12 + 3 k.
+FLOP_PER_PAIR_GRAD = 57.0
+FLOP_PER_PAIR_ENERGY = 21.0
+PEAK_FP32_VALU_TFLOPS = 157.3
+PEAK_HBM_GBS = 8000.0
+
+
+def frac_flop_per_pair(k: float) -> float:
+    return 12.0 + 3.0 * k
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", type=int, default=0, help="0 fp32 hi/lo, 1 fp32, 2 fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(mesh, u, target_s: float):
+    """The FP64 oracle timed on a bounded band of rows of the same step, scaled to the
+    whole step: t_step = F (t_grad / n_g + 2 t_frac / n_f) + 2 t_poisson."""
+    import numpy as np
+    import oracle as O
+
+    O.lib()
+    nF = mesh.nF
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    # calibrate on a small band, then size the bands to about target_s in total
+    t0 = time.perf_counter()
+    O.gradient_rows(mesh.V, mesh.F, 0, 32)
+    per_row_g = (time.perf_counter() - t0) / 32
+    t0 = time.perf_counter()
+    O.fractional_rows(mesh.V, mesh.F, u, 0, 32, 1.0 / 3.0)
+    per_row_f = (time.perf_counter() - t0) / 32
+    budget = max(1.0, 0.5 * target_s)
+    n_g = int(min(nF, max(64, budget * 0.7 / per_row_g)))
+    n_f = int(min(nF, max(64, budget * 0.3 / per_row_f)))
+    t0 = time.perf_counter()
+    O.gradient_rows(mesh.V, mesh.F, 0, n_g)
+    t_g = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.fractional_rows(mesh.V, mesh.F, u, 0, n_f, 1.0 / 3.0)
+    t_f = time.perf_counter() - t0
+    C = O.cotan_laplacian(mesh.V, mesh.F)
+    _, labels = O.components(mesh.F, mesh.nV)
+    t0 = time.perf_counter()
+    y = O.poisson_solve(C, u, labels)
+    t_p = time.perf_counter() - t0
+    t_step = nF * (t_g / n_g + 2.0 * t_f / n_f) + 2.0 * t_p
+    pairs = 3.0 * nF * (nF - 1)
+    return {
+        "value": pairs / t_step,
+        "unit": "tri-pair interactions/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": (f"oracle E+dE rows [0,{n_g}) of {nF} ({t_g:.2f} s), L^sigma rows [0,{n_f}) k=3 "
+                   f"({t_f:.2f} s), one sparse direct Poisson solve k=3 ({t_p:.2f} s); step time "
+                   f"extrapolated over all {nF} rows, 2 fractional applies, 2 solves = {t_step:.1f} s"),
+        "est_step_s": t_step,
+    }
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
+              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2107_01664_amd import meshgen as mg
+    from paper_2107_01664_amd import tpsurf as tp
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    tp.lib()
+    dev = torch.device("cuda", 0)
+    mesh = mg.workload("torus40k")
+    u_np = mg.random_columns(mesh.nV, 3, 1)
+    V = torch.from_numpy(mesh.V).to(dev)
+    F = torch.from_numpy(mesh.F).to(dev)
+    u = torch.from_numpy(u_np).to(dev)
+    nF = mesh.nF
+    params = tp.default_params(precision=a.precision)
+    P = tp.Problem(V, F, params)
+    dE = torch.empty((mesh.nV, 3), dtype=torch.float64, device=dev)
+    Lu = torch.empty_like(u)
+    x = torch.empty_like(dE)
+
+    def step():
+        E, _ = P.gradient(out=dE)
+        P.fractional_apply(u, out=Lu)
+        _, rep = P.precond_apply(dE, out=x)
+        return E, rep
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    tp.profile_reset()
+    tp.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = []
+    for _ in range(a.steps):
+        E, rep = step()
+        reps.append(rep)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tp.profile_enable(False)
+    ms_per_step = 1e3 * wall / a.steps
+    pairs_per_step = 3.0 * nF * (nF - 1)
+    value = pairs_per_step * a.steps / wall
+
+    g = tp.profile_get(tp.KIND_GRAD)
+    f = tp.profile_get(tp.KIND_FRAC)
+    grad_ms = g["ms_total"] / max(1, g["launches"])
+    grad_tflops = FLOP_PER_PAIR_GRAD * (g["pairs_total"] / max(1, g["launches"])) / (grad_ms * 1e-3) / 1e12
+    kfrac = f["cols_total"] / max(1.0, f["pairs_total"])
+    frac_ms = f["ms_total"] / max(1, f["launches"])
+    frac_tflops = frac_flop_per_pair(kfrac) * (f["pairs_total"] / max(1, f["launches"])) / (frac_ms * 1e-3) / 1e12
+    cg_ms = [float(np.mean([r.t_ms[0] for r in reps])), float(np.mean([r.t_ms[2] for r in reps]))]
+
+    out = {
+        "metric": "tri-pair interactions/s (E+dE, H-apply) vs FP32 roofline",
+        "value": value,
+        "unit": "tri-pair interactions/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {0: "fp32", 1: "fp32", 2: "f64"}[a.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": ("torus40k: torus R=1 r=0.3 on a 200x100 grid (40,000 faces), vertex noise "
+                         "0.002 r seed 0; per step E+dE, L^sigma u (u~N(0,1), k=3), and "
+                         "C^-1 L^sigma C^-1 dE with two FP64 CG solves to 1e-10"),
+            "faces": nF,
+            "vertices": mesh.nV,
+            "alpha": 6, "beta": 12, "sigma": 1.0 / 3.0,
+            "precision": {0: "fp32 pair terms, hi/lo barycenters, fp64 accumulation",
+                          1: "fp32 pair terms, fp64 accumulation",
+                          2: "fp64 pair terms"}[a.precision],
+            "pairs_per_step": pairs_per_step,
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "all-pairs energy + differential",
+            "achieved": grad_tflops,
+            "peak": PEAK_FP32_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": grad_tflops / PEAK_FP32_VALU_TFLOPS,
+            "traffic": None,
+            "flop_per_pair": FLOP_PER_PAIR_GRAD,
+            "avg_launch_ms": grad_ms,
+            "launches": g["launches"],
+            "pairs_per_s": (g["pairs_total"] / max(1, g["launches"])) / (grad_ms * 1e-3),
+        },
+        "kernels": {
+            "fractional_apply": {
+                "avg_launch_ms": frac_ms, "columns": kfrac, "flop_per_pair": frac_flop_per_pair(kfrac),
+                "achieved_tflops": frac_tflops, "frac": frac_tflops / PEAK_FP32_VALU_TFLOPS,
+                "pairs_per_s": (f["pairs_total"] / max(1, f["launches"])) / (frac_ms * 1e-3),
+            },
+            "cg_ms": {"solve1": cg_ms[0], "solve2": cg_ms[1]},
+            "cg_iters": [int(reps[-1].cg_iters[0]), int(reps[-1].cg_iters[1])],
+        },
+        "energy": E,
+    }
+    P.close()
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(mesh, u_np, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

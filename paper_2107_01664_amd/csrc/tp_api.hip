@@ -157,6 +157,9 @@ struct tp_problem {
     DevBuf<int32_t> vf_off, vf_idx, tmp_i, tmp_j;
     DevBuf<int32_t> lap_off, lap_col, comp;
     DevBuf<double> lap_val, inv_count;
+    DevBuf<int32_t> ell_col;
+    DevBuf<double> ell_val;
+    int ell_w = 0;
     int64_t nnz = 0;
     int ncomp = 0;
 
@@ -165,7 +168,7 @@ struct tp_problem {
     // work
     DevBuf<double> part, gface, zbuf, scal, red, vol6, edge;
     DevBuf<char> ub;
-    DevBuf<double> cg_r, cg_q, cg_p, cg_red, cg_relres;
+    DevBuf<double> cg_Z, cg_p, cg_red, cg_relres;
     DevBuf<unsigned> cg_bar;
     DevBuf<int> cg_iters;
     DevBuf<double> R, Y, W1, W2, gbuf, dir, Vt, Vsave;
@@ -303,6 +306,16 @@ tp_status ensure_lap(tp_problem* P)
     TP_TRY(P->lap_col.ensure(std::max<int64_t>(nnz, 1), s));
     TP_TRY(P->lap_val.ensure(std::max<int64_t>(nnz, 1), s));
     TP_HIP(launch_lap_pattern_fill(P->nV, P->vf_off.p, P->tmp_j.p, P->lap_off.p, P->lap_col.p, s));
+    {
+        std::vector<int32_t> hoff(P->nV + 1);
+        TP_HIP(hipMemcpyAsync(hoff.data(), P->lap_off.p, sizeof(int32_t) * (P->nV + 1), hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        int w = 1;
+        for (int64_t v = 0; v < P->nV; ++v) w = std::max(w, hoff[v + 1] - hoff[v]);
+        P->ell_w = w;
+        TP_TRY(P->ell_col.ensure((size_t)w * P->nV, s));
+        TP_TRY(P->ell_val.ensure((size_t)w * P->nV, s));
+    }
 
     // connected components over the face graph
     std::vector<int32_t> hF(3 * P->nF);
@@ -350,6 +363,8 @@ tp_status ensure_cotan(tp_problem* P)
     if (!P->cotan_valid) {
         TP_HIP(launch_cotan_values(P->V.p, P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->lap_off.p,
                                    P->lap_col.p, P->lap_val.p, P->stream));
+        TP_HIP(launch_csr_to_ell(P->nV, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->ell_w,
+                                 P->ell_col.p, P->ell_val.p, P->stream));
         P->cotan_valid = true;
     }
     return TP_OK;
@@ -450,9 +465,8 @@ tp_status run_fractional(tp_problem* P, const double* u, int ldu, int k, double*
 tp_status ensure_cg(tp_problem* P, int k)
 {
     hipStream_t s = P->stream;
-    TP_TRY(P->cg_r.ensure((size_t)P->nV * k, s));
-    TP_TRY(P->cg_q.ensure((size_t)P->nV * k, s));
-    TP_TRY(P->cg_p.ensure((size_t)2 * P->nV * k, s));
+    TP_TRY(P->cg_Z.ensure(cg_state_doubles(P->nV, k), s));
+    TP_TRY(P->cg_p.ensure((size_t)P->nV * k, s));
     TP_TRY(P->cg_red.ensure(cg_red_doubles(k), s));
     TP_TRY(P->cg_bar.ensure(cg_bar_words(k), s));
     TP_TRY(P->cg_iters.ensure(std::max(k, 64), s));
@@ -469,9 +483,9 @@ tp_status run_cg(tp_problem* P, double* b, double* x, int k, int* it_max, double
     hipStream_t s = P->stream;
     TP_HIP(launch_project_mean(b, k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
     CgWork w;
-    w.r = P->cg_r.p; w.q = P->cg_q.p; w.p = P->cg_p.p; w.red = P->cg_red.p; w.bar = P->cg_bar.p;
+    w.Z = P->cg_Z.p; w.p = P->cg_p.p; w.red = P->cg_red.p; w.bar = P->cg_bar.p;
     w.iters = P->cg_iters.p; w.relres = P->cg_relres.p; w.flags = P->flags.p;
-    TP_HIP(launch_cg(P->nV, P->lap_off.p, P->lap_col.p, P->lap_val.p, b, x, k, P->prm.cg_rtol,
+    TP_HIP(launch_cg(P->nV, P->ell_col.p, P->ell_val.p, P->ell_w, b, x, k, P->prm.cg_rtol,
                      P->prm.cg_maxiter, w, s));
     TP_HIP(launch_project_mean(x, k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
     std::vector<int> its(k);

@@ -1,38 +1,52 @@
 // Persistent FP64 conjugate gradients for the Poisson solves of the preconditioner
 // (Sec. 5.2: A~^{-1} = C^{-1} L^sigma C^{-1}, with C the cotan stiffness matrix).
 //
-// One cooperative launch solves k right-hand sides.  Columns are split into groups of KG;
-// group g is served by the workgroups with blockIdx % ngroups == g, which partition the
-// rows into contiguous chunks.  Workgroups of a group synchronise through a counter /
-// generation barrier in global memory (agent-scope atomics), so the launch needs no host
-// round trip per iteration.  Each iteration uses two barriers:
-//   1. q = C p_new with p_new = r + beta p_old formed on the fly from the previous
-//      iteration's r and p_old (p is double-buffered, so no workgroup overwrites values
-//      another workgroup may still read), local p.q sums   -> barrier, alpha = r.r / p.q
-//   2. x += alpha p_new, r -= alpha q, local r.r sums        -> barrier, beta, convergence
-// Every workgroup adds the per-workgroup partial sums in the same order, so all of them
-// take identical decisions and the result does not depend on scheduling.  Spins are
-// bounded: a barrier that waits too long raises an abort flag and every workgroup exits.
+// The recurrence is Chronopoulos-Gear CG: both inner products of an iteration,
+// gamma = (r, r) and delta = (w, r) with w = C r, come from one reduction, so an iteration
+// needs a single grid-wide exchange:
+//   p_i = r_i + beta_i p_{i-1},  s_i = w_i + beta_i s_{i-1}   (s_i = C p_i)
+//   x_{i+1} = x_i + alpha_i p_i, r_{i+1} = r_i - alpha_i s_i, w_{i+1} = C r_{i+1}
+//   beta_{i+1} = gamma_{i+1} / gamma_i,
+//   alpha_{i+1} = gamma_{i+1} / (delta_{i+1} - beta_{i+1} gamma_{i+1} / alpha_i).
+// The sparse product needs r_{i+1} at neighbouring rows owned by other workgroups; it is
+// formed on the fly as r_i - alpha_i (w_i + beta_i s_{i-1}) from the previous iteration's
+// values, which sit in one of two buffers (ping-pong by iteration parity), so no
+// workgroup overwrites what another may still read and no second barrier is needed.
+//
+// Layout: the matrix in column-major ELL (width = longest row, padded with the row's own
+// index and value 0); per row the state (r, w, s) of all k columns is contiguous,
+// Z[buf][row][3][k].  One thread per row handles all columns of its group.  Columns are
+// split into groups (blockIdx % ngroups); workgroups of a group meet at a two-level
+// counter barrier in global memory (agent-scope atomics) with bounded spins: a wait that
+// lasts too long raises an abort flag and every workgroup leaves the loop.  All
+// workgroups add the per-workgroup partial sums in the same order, so they take the same
+// decisions and the result does not depend on scheduling.
 #include "tp_internal.h"
+
+#include <algorithm>
 
 namespace tp {
 
 constexpr int kCgBlock = 256;
 constexpr unsigned long long kSpinLimit = 1ull << 22;
-constexpr int kBarStride = 64;      // unsigned words between the barriers of two groups
+constexpr int kMaxW = 128;           // workgroups per column group
+constexpr int kMaxGroups = 8;
+constexpr int kLine = 32;            // unsigned words per 128-byte line
+// barrier words per group: 8 level-1 counters, 1 level-2 counter, 1 generation,
+// each on its own line
+constexpr int kBarWordsPerGroup = 10 * kLine;
 
 struct CgArgs {
     int64_t n;
-    const int32_t* off;
-    const int32_t* col;
-    const double* val;
-    const double* b;
-    double* x;
-    double* r;
-    double* q;
-    double* p;            // [2][n * k]
-    double* red;          // [ngroups][2][W][KG]
-    unsigned* bar;        // [ngroups][kBarStride]
+    int ell_w;
+    const int32_t* ecol;   // [ell_w][n]
+    const double* eval;    // [ell_w][n]
+    const double* b;       // [n][k]
+    double* x;             // [n][k]
+    double* Z;             // [2][n][3][k]
+    double* p;             // [n][k]
+    double* red;           // [ngroups][2][W][2][KG]
+    unsigned* bar;         // [ngroups][kBarWordsPerGroup]
     int* iters;
     double* relres;
     int* flags;
@@ -41,21 +55,38 @@ struct CgArgs {
     int k;
     int ngroups;
     int W;
+    int rows_per_thread;
 };
 
-__device__ bool group_barrier(unsigned* cnt, unsigned* gen, unsigned W, int* flags)
+// Two-level barrier among the W workgroups of a group: workgroup w first arrives at
+// counter (w % 8); the last of that set arrives at the group counter; the last of those
+// advances the generation word that everybody waits on.
+__device__ bool group_barrier(unsigned* gbar, int w, int W, int* flags)
 {
     __shared__ int ok_sh;
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
+        unsigned* gen = gbar + 9 * kLine;
+        unsigned* top = gbar + 8 * kLine;
+        const int sub = w & 7;
+        const int nsub = (W + 7 - sub) / 8;           // members of this level-1 set
+        const int ntop = W < 8 ? W : 8;                 // non-empty level-1 sets
         __threadfence();
         const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned prev = __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev + 1 == W) {
-            __hip_atomic_store(cnt, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
+        unsigned* c1 = gbar + sub * kLine;
+        const unsigned a1 = __hip_atomic_fetch_add(c1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        bool last = false;
+        if ((int)a1 + 1 == nsub) {
+            __hip_atomic_store(c1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned a2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if ((int)a2 + 1 == ntop) {
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                last = true;
+            }
+        }
+        if (!last) {
             unsigned long long spins = 0;
             while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
                 __builtin_amdgcn_s_sleep(1);
@@ -80,22 +111,23 @@ __device__ bool group_barrier(unsigned* cnt, unsigned* gen, unsigned W, int* fla
     return ok_sh != 0;
 }
 
-// Sum v over the workgroup for each of KG columns; result valid in sh_out[0..KG).
+// Workgroup sums of two KG-vectors (fixed butterfly, then waves in order) into sh_out.
 template <int KG>
-__device__ __forceinline__ void block_sums(const double (&v)[KG], double* sh_wave, double* sh_out)
+__device__ __forceinline__ void block_sums2(const double (&a)[KG], const double (&b)[KG],
+                                            double* sh_wave, double* sh_out)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int c = 0; c < KG; ++c) {
-        double s = v[c];
+    for (int c = 0; c < 2 * KG; ++c) {
+        double s = c < KG ? a[c] : b[c - KG];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (lane == 0) sh_wave[wave * KG + c] = s;
+        if (lane == 0) sh_wave[wave * 2 * KG + c] = s;
     }
     __syncthreads();
-    if (threadIdx.x < KG) {
+    if (threadIdx.x < 2 * KG) {
         double s = 0.0;
-        for (int w = 0; w < kCgBlock / 64; ++w) s += sh_wave[w * KG + threadIdx.x];
+        for (int w = 0; w < kCgBlock / 64; ++w) s += sh_wave[w * 2 * KG + threadIdx.x];
         sh_out[threadIdx.x] = s;
     }
     __syncthreads();
@@ -104,65 +136,102 @@ __device__ __forceinline__ void block_sums(const double (&v)[KG], double* sh_wav
 template <int KG>
 __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs A)
 {
-    __shared__ double sh_wave[(kCgBlock / 64) * KG];
-    __shared__ double sh_sum[KG];
-    __shared__ double sh_grp[KG];
+    __shared__ double sh_wave[(kCgBlock / 64) * 2 * KG];
+    __shared__ double sh_sum[2 * KG];
+    __shared__ double sh_grp[2 * KG];
 
     const int g = blockIdx.x % A.ngroups;
     const int w = blockIdx.x / A.ngroups;
     const int c0 = g * KG;
     const int nc = min(KG, A.k - c0);
     const int k = A.k;
-    const int64_t chunk = (A.n + A.W - 1) / A.W;
-    const int64_t rb = (int64_t)w * chunk, re = min(A.n, rb + chunk);
-    unsigned* cnt = A.bar + (int64_t)g * kBarStride;
-    unsigned* gen = cnt + kBarStride / 2;
-    double* red0 = A.red + ((int64_t)g * 2 + 0) * A.W * KG;
-    double* red1 = A.red + ((int64_t)g * 2 + 1) * A.W * KG;
-    double* p0 = A.p;
-    double* p1 = A.p + A.n * k;
+    const int64_t n = A.n;
+    const int64_t rows_per_wg = (int64_t)kCgBlock * A.rows_per_thread;
+    const int64_t rb = (int64_t)w * rows_per_wg;
+    const int64_t re = min(n, rb + rows_per_wg);
+    unsigned* gbar = A.bar + (int64_t)g * kBarWordsPerGroup;
+    double* redg = A.red + (int64_t)g * 2 * A.W * 2 * KG;
+    const int64_t zrow = 3 * (int64_t)k;             // doubles per row of Z
+    double* Z0 = A.Z;
+    double* Z1 = A.Z + n * zrow;
 
-    // Group-wide sum of the per-workgroup partials in workgroup order.
-    auto group_sum = [&](double* red) {
-        if (threadIdx.x < KG) {
+    // Group-wide sums of the per-workgroup partials: every thread loads its share of the
+    // W x 2KG partials at once, then thread c adds column c over the workgroups in order.
+    __shared__ double sh_red[kMaxW * 2 * KG];
+    auto group_sum = [&](const double* red) {
+        const int tot = A.W * 2 * KG;
+        for (int t = threadIdx.x; t < tot; t += kCgBlock) sh_red[t] = red[t];
+        __syncthreads();
+        if (threadIdx.x < 2 * KG) {
             double s = 0.0;
-            for (int ww = 0; ww < A.W; ++ww) s += red[ww * KG + threadIdx.x];
+            for (int ww = 0; ww < A.W; ++ww) s += sh_red[ww * 2 * KG + threadIdx.x];
             sh_grp[threadIdx.x] = s;
         }
         __syncthreads();
     };
 
-    double loc[KG];
+    // The matrix does not change during the solve: with one row per thread, keep the
+    // first kCache entries of the row in registers.
+    constexpr int kCache = 8;
+    const bool cached = A.rows_per_thread == 1;
+    int32_t cj[kCache];
+    double cv[kCache];
+    {
+        const int64_t i = rb + threadIdx.x;
 #pragma unroll
-    for (int c = 0; c < KG; ++c) loc[c] = 0.0;
+        for (int e = 0; e < kCache; ++e) {
+            const bool in = cached && i < re && e < A.ell_w;
+            cj[e] = in ? A.ecol[(int64_t)e * n + i] : 0;
+            cv[e] = in ? A.eval[(int64_t)e * n + i] : 0.0;
+        }
+    }
+
+    // ---- initial state: x0 = 0, r0 = b, w0 = C b, s_{-1} = p_{-1} = 0
+    double ga[KG], de[KG];
+#pragma unroll
+    for (int c = 0; c < KG; ++c) ga[c] = de[c] = 0.0;
     for (int64_t i = rb + threadIdx.x; i < re; i += kCgBlock) {
+        double acc[KG];
+#pragma unroll
+        for (int c = 0; c < KG; ++c) acc[c] = 0.0;
+        for (int e = 0; e < A.ell_w; ++e) {
+            const int64_t j = A.ecol[(int64_t)e * n + i];
+            const double v = A.eval[(int64_t)e * n + i];
+#pragma unroll
+            for (int c = 0; c < KG; ++c)
+                if (c < nc) acc[c] += v * A.b[j * k + c0 + c];
+        }
+        double* zi = Z0 + i * zrow;
 #pragma unroll
         for (int c = 0; c < KG; ++c) {
             if (c < nc) {
-                const int64_t id = i * k + c0 + c;
-                const double bv = A.b[id];
-                A.x[id] = 0.0;
-                A.r[id] = bv;
-                p0[id] = 0.0;
-                loc[c] += bv * bv;
+                const double bv = A.b[i * k + c0 + c];
+                A.x[i * k + c0 + c] = 0.0;
+                A.p[i * k + c0 + c] = 0.0;
+                zi[c0 + c] = bv;               // r
+                zi[k + c0 + c] = acc[c];       // w
+                zi[2 * k + c0 + c] = 0.0;      // s
+                ga[c] += bv * bv;
+                de[c] += acc[c] * bv;
             }
         }
     }
-    block_sums<KG>(loc, sh_wave, sh_sum);
-    if (threadIdx.x < KG) red0[w * KG + threadIdx.x] = sh_sum[threadIdx.x];
-    if (!group_barrier(cnt, gen, (unsigned)A.W, A.flags)) return;
-    group_sum(red0);
+    block_sums2<KG>(ga, de, sh_wave, sh_sum);
+    if (threadIdx.x < 2 * KG) redg[(0 * A.W + w) * 2 * KG + threadIdx.x] = sh_sum[threadIdx.x];
+    if (!group_barrier(gbar, w, A.W, A.flags)) return;
+    group_sum(redg);
 
-    double rr[KG], bb[KG], beta[KG], alpha[KG];
+    double gam[KG], bb[KG], alpha[KG], beta[KG];
     bool done[KG];
     int its[KG];
 #pragma unroll
     for (int c = 0; c < KG; ++c) {
-        rr[c] = sh_grp[c];
-        bb[c] = rr[c];
+        gam[c] = sh_grp[c];
+        const double d0 = sh_grp[KG + c];
+        bb[c] = gam[c];
         beta[c] = 0.0;
-        alpha[c] = 0.0;
         done[c] = (c >= nc) || !(bb[c] > 0.0);
+        alpha[c] = done[c] ? 0.0 : gam[c] / d0;
         its[c] = 0;
     }
     __syncthreads();
@@ -172,69 +241,71 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs A)
 #pragma unroll
         for (int c = 0; c < KG; ++c) all = all && done[c];
         if (all) break;
-        double* pold = (it & 1) ? p1 : p0;
-        double* pnew = (it & 1) ? p0 : p1;
-
-        // 1. p_new = r + beta p_old (own rows); q = C p_new from the previous values.
+        const double* Zc = (it & 1) ? Z1 : Z0;
+        double* Zn = (it & 1) ? Z0 : Z1;
 #pragma unroll
-        for (int c = 0; c < KG; ++c) loc[c] = 0.0;
+        for (int c = 0; c < KG; ++c) ga[c] = de[c] = 0.0;
         for (int64_t i = rb + threadIdx.x; i < re; i += kCgBlock) {
+            // w_{i+1} = C r_{i+1}, with r_{i+1}(j) = r_i(j) - alpha (w_i(j) + beta s_{i-1}(j))
             double acc[KG];
 #pragma unroll
             for (int c = 0; c < KG; ++c) acc[c] = 0.0;
-            for (int32_t e = A.off[i]; e < A.off[i + 1]; ++e) {
-                const int64_t jb = (int64_t)A.col[e] * k + c0;
-                const double v = A.val[e];
+            auto add_entry = [&](int64_t j, double v) {
+                const double* zj = Zc + j * zrow + c0;
 #pragma unroll
                 for (int c = 0; c < KG; ++c)
-                    if (c < nc) acc[c] += v * (A.r[jb + c] + beta[c] * pold[jb + c]);
+                    if (c < nc) acc[c] += v * (zj[c] - alpha[c] * (zj[k + c] + beta[c] * zj[2 * k + c]));
+            };
+            int e0 = 0;
+            if (cached) {
+#pragma unroll
+                for (int e = 0; e < kCache; ++e)
+                    if (e < A.ell_w) add_entry(cj[e], cv[e]);
+                e0 = kCache;
             }
+            for (int e = e0; e < A.ell_w; ++e)
+                add_entry(A.ecol[(int64_t)e * n + i], A.eval[(int64_t)e * n + i]);
+            const double* zi = Zc + i * zrow + c0;
+            double* zo = Zn + i * zrow + c0;
 #pragma unroll
             for (int c = 0; c < KG; ++c) {
                 if (c < nc) {
                     const int64_t id = i * k + c0 + c;
-                    const double pn = A.r[id] + beta[c] * pold[id];
-                    pnew[id] = pn;
-                    A.q[id] = acc[c];
-                    loc[c] += pn * acc[c];
+                    const double r = zi[c], wv = zi[k + c], s = zi[2 * k + c];
+                    const double pn = r + beta[c] * A.p[id];
+                    const double sn = wv + beta[c] * s;
+                    A.p[id] = pn;
+                    A.x[id] += alpha[c] * pn;
+                    const double rn = r - alpha[c] * sn;
+                    zo[c] = rn;
+                    zo[k + c] = acc[c];
+                    zo[2 * k + c] = sn;
+                    ga[c] += rn * rn;
+                    de[c] += acc[c] * rn;
                 }
             }
         }
-        block_sums<KG>(loc, sh_wave, sh_sum);
-        if (threadIdx.x < KG) red1[w * KG + threadIdx.x] = sh_sum[threadIdx.x];
-        if (!group_barrier(cnt, gen, (unsigned)A.W, A.flags)) return;
-        group_sum(red1);
-#pragma unroll
-        for (int c = 0; c < KG; ++c) alpha[c] = done[c] ? 0.0 : rr[c] / sh_grp[c];
-        __syncthreads();
-
-        // 2. x += alpha p_new, r -= alpha q.
-#pragma unroll
-        for (int c = 0; c < KG; ++c) loc[c] = 0.0;
-        for (int64_t i = rb + threadIdx.x; i < re; i += kCgBlock) {
-#pragma unroll
-            for (int c = 0; c < KG; ++c) {
-                if (c < nc) {
-                    const int64_t id = i * k + c0 + c;
-                    A.x[id] += alpha[c] * pnew[id];
-                    const double rn = A.r[id] - alpha[c] * A.q[id];
-                    A.r[id] = rn;
-                    loc[c] += rn * rn;
-                }
-            }
-        }
-        block_sums<KG>(loc, sh_wave, sh_sum);
-        if (threadIdx.x < KG) red0[w * KG + threadIdx.x] = sh_sum[threadIdx.x];
-        if (!group_barrier(cnt, gen, (unsigned)A.W, A.flags)) return;
-        group_sum(red0);
+        block_sums2<KG>(ga, de, sh_wave, sh_sum);
+        double* red = redg + (int64_t)((it + 1) & 1) * A.W * 2 * KG;
+        if (threadIdx.x < 2 * KG) red[w * 2 * KG + threadIdx.x] = sh_sum[threadIdx.x];
+        if (!group_barrier(gbar, w, A.W, A.flags)) return;
+        group_sum(red);
 #pragma unroll
         for (int c = 0; c < KG; ++c) {
             if (!done[c]) {
-                const double rn = sh_grp[c];
+                const double gn = sh_grp[c], dn = sh_grp[KG + c];
                 its[c] = it + 1;
-                beta[c] = rn / rr[c];
-                rr[c] = rn;
-                if (sqrt(rn / bb[c]) <= A.rtol) done[c] = true;
+                const double bn = gn / gam[c];
+                const double an = gn / (dn - bn * gn / alpha[c]);
+                gam[c] = gn;
+                if (sqrt(gn / bb[c]) <= A.rtol) {
+                    done[c] = true;
+                    alpha[c] = 0.0;
+                    beta[c] = 0.0;
+                } else {
+                    beta[c] = bn;
+                    alpha[c] = an;
+                }
             }
         }
         __syncthreads();
@@ -242,68 +313,99 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs A)
     if (w == 0 && threadIdx.x < nc) {
         const int c = threadIdx.x;
         A.iters[c0 + c] = its[c];
-        A.relres[c0 + c] = bb[c] > 0.0 ? sqrt(rr[c] / bb[c]) : 0.0;
+        A.relres[c0 + c] = bb[c] > 0.0 ? sqrt(gam[c] / bb[c]) : 0.0;
     }
 }
+
+// ------------------------------------------------------------------ CSR -> ELL
+
+__global__ void k_csr_to_ell(int64_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ col,
+                             const double* __restrict__ val, int w, int32_t* __restrict__ ecol,
+                             double* __restrict__ eval)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int32_t b = off[i], len = off[i + 1] - b;
+    for (int e = 0; e < w; ++e) {
+        const bool in = e < len;
+        ecol[(int64_t)e * n + i] = in ? col[b + e] : (int32_t)i;
+        eval[(int64_t)e * n + i] = in ? val[b + e] : 0.0;
+    }
+}
+
+hipError_t launch_csr_to_ell(int64_t n, const int32_t* off, const int32_t* col, const double* val,
+                             int w, int32_t* ecol, double* eval, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_csr_to_ell, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, off, col, val, w, ecol, eval);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ launch
 
 namespace {
 
 struct CgShape {
-    int kg, ngroups, W;
+    int kg, ngroups;
 };
 
-CgShape cg_shape(int64_t n, int k)
+CgShape cg_shape(int k)
 {
     CgShape s;
-    s.kg = (k + 7) / 8;                       // at most 8 groups
-    if (s.kg > kMaxGroupCols) s.kg = kMaxGroupCols;
-    s.ngroups = (k + s.kg - 1) / s.kg;
-    int64_t W = (n + 2047) / 2048;
-    if (W < 1) W = 1;
-    if (W > 32) W = 32;
-    s.W = (int)W;
+    s.ngroups = (k + kMaxGroupCols - 1) / kMaxGroupCols;
+    s.kg = (k + s.ngroups - 1) / s.ngroups;
     return s;
 }
 
+// Rows per thread and workgroups per group: one row per thread while the group fits in
+// kMaxW workgroups and the whole grid stays co-resident (a cooperative launch needs it).
 template <int KG>
-hipError_t launch_cg_k(const CgArgs& a, hipStream_t s)
+hipError_t launch_cg_k(CgArgs a, hipStream_t s)
 {
     const void* fn = (const void*)k_cg<KG>;
     int per_cu = 0;
     hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kCgBlock, 0);
     if (e != hipSuccess) return e;
-    const int64_t total = (int64_t)a.ngroups * a.W;
-    if (total > (int64_t)per_cu * device_info().num_cu) return hipErrorCooperativeLaunchTooLarge;
-    CgArgs args = a;
-    void* params[] = {&args};
-    return hipLaunchCooperativeKernel(fn, dim3((unsigned)total), dim3(kCgBlock), params, 0, s);
+    const int64_t capacity = (int64_t)per_cu * device_info().num_cu;
+    const int64_t wmax = std::min<int64_t>(kMaxW, capacity / a.ngroups);
+    if (wmax < 1) return hipErrorCooperativeLaunchTooLarge;
+    const int64_t wg_rows = (a.n + kCgBlock - 1) / kCgBlock;
+    a.rows_per_thread = (int)((wg_rows + wmax - 1) / wmax);
+    a.W = (int)((a.n + (int64_t)kCgBlock * a.rows_per_thread - 1) / ((int64_t)kCgBlock * a.rows_per_thread));
+    if (a.W < 1) a.W = 1;
+    void* params[] = {&a};
+    return hipLaunchCooperativeKernel(fn, dim3((unsigned)(a.ngroups * a.W)), dim3(kCgBlock), params, 0, s);
 }
 
 }  // namespace
 
 size_t cg_red_doubles(int k)
 {
-    return (size_t)8 * 2 * 32 * kMaxGroupCols + (size_t)k;
+    (void)k;
+    return (size_t)kMaxGroups * 2 * kMaxW * 2 * kMaxGroupCols;
 }
 
 size_t cg_bar_words(int k)
 {
     (void)k;
-    return (size_t)8 * kBarStride;
+    return (size_t)kMaxGroups * kBarWordsPerGroup;
 }
 
-hipError_t launch_cg(int64_t n, const int32_t* off, const int32_t* col, const double* val,
+size_t cg_state_doubles(int64_t n, int k) { return (size_t)2 * n * 3 * k; }
+
+hipError_t launch_cg(int64_t n, const int32_t* ecol, const double* eval, int ell_w,
                      const double* b, double* x, int k, double rtol, int maxiter,
                      const CgWork& w, hipStream_t s)
 {
-    const CgShape sh = cg_shape(n, k);
+    const CgShape sh = cg_shape(k);
+    if (sh.ngroups > kMaxGroups || sh.kg > kMaxGroupCols) return hipErrorInvalidValue;
     hipError_t e = hipMemsetAsync(w.bar, 0, cg_bar_words(k) * sizeof(unsigned), s);
     if (e != hipSuccess) return e;
     CgArgs a;
-    a.n = n; a.off = off; a.col = col; a.val = val; a.b = b; a.x = x;
-    a.r = w.r; a.q = w.q; a.p = w.p; a.red = w.red; a.bar = w.bar;
+    a.n = n; a.ell_w = ell_w; a.ecol = ecol; a.eval = eval; a.b = b; a.x = x;
+    a.Z = w.Z; a.p = w.p; a.red = w.red; a.bar = w.bar;
     a.iters = w.iters; a.relres = w.relres; a.flags = w.flags;
-    a.rtol = rtol; a.maxiter = maxiter; a.k = k; a.ngroups = sh.ngroups; a.W = sh.W;
+    a.rtol = rtol; a.maxiter = maxiter; a.k = k; a.ngroups = sh.ngroups; a.W = 1;
+    a.rows_per_thread = 1;
     switch (sh.kg) {
     case 1: return launch_cg_k<1>(a, s);
     case 2: return launch_cg_k<2>(a, s);

@@ -158,22 +158,24 @@ hipError_t launch_axpy_block3(int64_t n, const double* x, int ldx, double a,
 hipError_t launch_copy_cols(int64_t n, const double* x, int ldx, int k, double* y, int ldy,
                             hipStream_t s);
 
-// Persistent FP64 conjugate gradients on k columns (row-major [n][k]).  x gets the
-// solution of C x = b (b must be per-component mean zero); iters / relres per column
-// are written to device arrays.  Work arrays: r, q [n][k]; p two buffers [2][n][k].
+// Persistent FP64 conjugate gradients on k columns (row-major [n][k]) with the matrix in
+// column-major ELL form.  x gets the solution of C x = b (b must be per-component mean
+// zero); iteration counts and final relative residuals per column go to device arrays.
 struct CgWork {
-    double* r = nullptr;
-    double* q = nullptr;
-    double* p = nullptr;        // 2 * n * k
-    double* red = nullptr;      // reduction scratch
-    unsigned* bar = nullptr;    // barrier words
+    double* Z = nullptr;        // cg_state_doubles(n, k)
+    double* p = nullptr;        // n * k
+    double* red = nullptr;      // cg_red_doubles(k)
+    unsigned* bar = nullptr;    // cg_bar_words(k)
     int* iters = nullptr;       // k
     double* relres = nullptr;   // k
     int* flags = nullptr;       // device error flags
 };
 size_t cg_red_doubles(int k);
 size_t cg_bar_words(int k);
-hipError_t launch_cg(int64_t n, const int32_t* off, const int32_t* col, const double* val,
+size_t cg_state_doubles(int64_t n, int k);
+hipError_t launch_csr_to_ell(int64_t n, const int32_t* off, const int32_t* col, const double* val,
+                             int w, int32_t* ecol, double* eval, hipStream_t s);
+hipError_t launch_cg(int64_t n, const int32_t* ecol, const double* eval, int ell_w,
                      const double* b, double* x, int k, double rtol, int maxiter,
                      const CgWork& w, hipStream_t s);
 
