@@ -78,6 +78,9 @@ typedef struct {
     int    precision;    /* tp_precision, default TP_PREC_FP32_HILO                      */
     double cg_rtol;      /* CG stops when ||b - C x|| <= cg_rtol ||b||, default 1e-10   */
     int    cg_maxiter;   /* default 20000                                               */
+    int    cg_precond;   /* 1: two-level additive Schwarz preconditioner (default, used
+                            when the mesh has at most 256 blocks of 128 vertices);
+                            0: unpreconditioned CG                                        */
 } tp_params;
 
 /* Fill *p with the defaults above. */
@@ -144,6 +147,13 @@ TP_API tp_status tp_problem_gradient(tp_problem* prob, double* E_out, double* dE
 TP_API tp_status tp_problem_fractional_apply(tp_problem* prob, const double* u, int k, double* Lu_out);
 TP_API tp_status tp_problem_precond_apply(tp_problem* prob, const double* b, int k, double* x_out,
                                    tp_solve_report* report);
+
+/* x = C^+ P b columnwise: the per-component mean-zero solution of the cotan Poisson
+ * problem C x = P b by FP64 CG (one of the two solves inside A~^{-1}, Sec. 5.2).
+ * b, x_out: device, nV x k row-major, 1 <= k <= 64.  report (may be NULL) receives the
+ * largest iteration count and final true relative residual in cg_iters[0], cg_relres[0]. */
+TP_API tp_status tp_problem_poisson_solve(tp_problem* prob, const double* b, int k, double* x_out,
+                                          tp_solve_report* report);
 
 /* Options of one descent step. */
 typedef struct {

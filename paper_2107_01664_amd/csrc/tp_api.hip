@@ -160,6 +160,15 @@ struct tp_problem {
     DevBuf<int32_t> ell_col;
     DevBuf<double> ell_val;
     int ell_w = 0;
+
+    // two-level Schwarz preconditioner (block order, dense block inverses, coarse inverse)
+    bool have_pcg = false;
+    PcgSetup pcg;
+    DevBuf<int32_t> pcg_perm, pcg_pcol, pcg_bstart, pcg_badj_off, pcg_badj, pcg_whole, pcg_blk,
+        pcg_bcomp, pcg_ncb;
+    DevBuf<uint8_t> pcg_pslot;
+    DevBuf<float> pcg_Binv;
+    DevBuf<double> pcg_pval, pcg_C0inv, pcg_Vb, pcg_rho, pcg_red, pcg_bp, pcg_xp;
     int64_t nnz = 0;
     int ncomp = 0;
 
@@ -203,6 +212,7 @@ tp_status validate_params(const tp_params* in, tp_params& out, double& sigma)
     if (out.precision < 0 || out.precision > 2) return fail(TP_E_INVALID_ARGUMENT, "unknown precision");
     if (!(out.cg_rtol > 0.0)) return fail(TP_E_INVALID_ARGUMENT, "cg_rtol must be > 0");
     if (out.cg_maxiter < 1) return fail(TP_E_INVALID_ARGUMENT, "cg_maxiter must be >= 1");
+    if (out.cg_precond != 0 && out.cg_precond != 1) return fail(TP_E_INVALID_ARGUMENT, "cg_precond must be 0 or 1");
     sigma = out.sigma;
     if (sigma < 0.0) {
         const double s = (out.beta - 2.0) / out.alpha;   // s = 2 - 2/p when beta = 2 alpha
@@ -289,6 +299,139 @@ tp_status ensure_vf(tp_problem* P)
     return TP_OK;
 }
 
+// Block partition for the preconditioner: vertices ordered by (component, Morton code
+// of the position in the component's bounding box), each component cut into equal blocks
+// of at most pcg_block_size() consecutive vertices.  Builds the permuted ELL pattern, the
+// neighbouring-block lists and the per-block / per-component tables.
+tp_status build_pcg(tp_problem* P, const std::vector<int32_t>& label, int ncomp,
+                    const std::vector<int32_t>& hoff, const std::vector<int32_t>& hcol)
+{
+    hipStream_t s = P->stream;
+    const int64_t n = P->nV;
+    const int BS = pcg_block_size();
+    std::vector<double> hV(3 * n);
+    TP_HIP(hipMemcpyAsync(hV.data(), P->V.p, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    std::vector<double> lo(3 * ncomp, 1e300), hi(3 * ncomp, -1e300);
+    for (int64_t v = 0; v < n; ++v)
+        for (int d = 0; d < 3; ++d) {
+            lo[3 * label[v] + d] = std::min(lo[3 * label[v] + d], hV[3 * v + d]);
+            hi[3 * label[v] + d] = std::max(hi[3 * label[v] + d], hV[3 * v + d]);
+        }
+    auto spread = [](uint64_t x) {   // 21 bits -> every third bit
+        x &= 0x1fffff;
+        x = (x | x << 32) & 0x1f00000000ffffull;
+        x = (x | x << 16) & 0x1f0000ff0000ffull;
+        x = (x | x << 8) & 0x100f00f00f00f00full;
+        x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+        x = (x | x << 2) & 0x1249249249249249ull;
+        return x;
+    };
+    std::vector<uint64_t> key(n);
+    for (int64_t v = 0; v < n; ++v) {
+        uint64_t code = 0;
+        for (int d = 0; d < 3; ++d) {
+            const double l = lo[3 * label[v] + d], h = hi[3 * label[v] + d];
+            const double t = h > l ? (hV[3 * v + d] - l) / (h - l) : 0.0;
+            const uint64_t q = (uint64_t)std::min(2097151.0, std::max(0.0, t * 2097151.0));
+            code |= spread(q) << d;
+        }
+        key[v] = code;
+    }
+    std::vector<int32_t> perm(n);
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+        if (label[a] != label[b]) return label[a] < label[b];
+        return key[a] < key[b];
+    });
+    std::vector<int32_t> iperm(n);
+    for (int64_t i = 0; i < n; ++i) iperm[perm[i]] = (int32_t)i;
+    // blocks: each component [c0, c1) in the new order cut into ceil(m / BS) equal parts
+    std::vector<int32_t> bstart, bcomp, whole, ncb(ncomp, 0);
+    int64_t pos = 0;
+    while (pos < n) {
+        const int c = label[perm[pos]];
+        int64_t end = pos;
+        while (end < n && label[perm[end]] == c) ++end;
+        const int64_t m = end - pos;
+        const int64_t nbc = (m + BS - 1) / BS;
+        for (int64_t q = 0; q < nbc; ++q) {
+            bstart.push_back((int32_t)(pos + q * m / nbc));
+            bcomp.push_back(c);
+            whole.push_back(nbc == 1 ? 1 : 0);
+            ncb[c] += 1;
+        }
+        pos = end;
+    }
+    const int nb = (int)bstart.size();
+    bstart.push_back((int32_t)n);
+    P->have_pcg = false;
+    if (!pcg_supported(nb, 0)) return TP_OK;          // too many blocks: plain CG
+    std::vector<int32_t> blk(n);
+    for (int b = 0; b < nb; ++b)
+        for (int32_t i = bstart[b]; i < bstart[b + 1]; ++i) blk[i] = b;
+    // neighbouring blocks
+    std::vector<int32_t> badj_off(1, 0), badj;
+    for (int b = 0; b < nb; ++b) {
+        std::vector<int32_t> lst;
+        for (int32_t i = bstart[b]; i < bstart[b + 1]; ++i) {
+            const int32_t old = perm[i];
+            for (int32_t q = hoff[old]; q < hoff[old + 1]; ++q) lst.push_back(blk[iperm[hcol[q]]]);
+        }
+        lst.push_back(b);
+        std::sort(lst.begin(), lst.end());
+        lst.erase(std::unique(lst.begin(), lst.end()), lst.end());
+        if ((int)lst.size() > pcg_max_neighbors()) return TP_OK;   // plain CG
+        badj.insert(badj.end(), lst.begin(), lst.end());
+        badj_off.push_back((int32_t)badj.size());
+    }
+    // permuted ELL pattern and block slots
+    const int w = P->ell_w;
+    std::vector<int32_t> pcol((size_t)w * n);
+    std::vector<uint8_t> pslot((size_t)w * n);
+    for (int64_t i = 0; i < n; ++i) {
+        const int32_t old = perm[i];
+        const int32_t b = hoff[old], len = hoff[old + 1] - b;
+        const int bi = blk[i];
+        for (int e = 0; e < w; ++e) {
+            const int32_t j = e < len ? iperm[hcol[b + e]] : (int32_t)i;
+            pcol[(size_t)e * n + i] = j;
+            const int bj = blk[j];
+            int sl = 0;
+            for (int q = badj_off[bi]; q < badj_off[bi + 1]; ++q)
+                if (badj[q] == bj) sl = q - badj_off[bi];
+            pslot[(size_t)e * n + i] = (uint8_t)sl;
+        }
+    }
+    auto up = [&](auto& buf, const auto& host) -> tp_status {
+        TP_TRY(buf.ensure(std::max<size_t>(host.size(), 1), s));
+        TP_HIP(hipMemcpyAsync(buf.p, host.data(), sizeof(host[0]) * host.size(), hipMemcpyHostToDevice, s));
+        return TP_OK;
+    };
+    TP_TRY(up(P->pcg_perm, perm));
+    TP_TRY(up(P->pcg_pcol, pcol));
+    TP_TRY(up(P->pcg_pslot, pslot));
+    TP_TRY(up(P->pcg_bstart, bstart));
+    TP_TRY(up(P->pcg_badj_off, badj_off));
+    TP_TRY(up(P->pcg_badj, badj));
+    TP_TRY(up(P->pcg_whole, whole));
+    TP_TRY(up(P->pcg_blk, blk));
+    TP_TRY(up(P->pcg_bcomp, bcomp));
+    TP_TRY(up(P->pcg_ncb, ncb));
+    TP_TRY(P->pcg_pval.ensure((size_t)w * n, s));
+    TP_TRY(P->pcg_Binv.ensure((size_t)nb * BS * BS, s));
+    TP_TRY(P->pcg_C0inv.ensure((size_t)nb * nb, s));
+    TP_HIP(hipStreamSynchronize(s));
+    PcgSetup& ps = P->pcg;
+    ps.n = n; ps.nb = nb; ps.ell_w = w;
+    ps.perm = P->pcg_perm.p; ps.pcol = P->pcg_pcol.p; ps.pval = P->pcg_pval.p; ps.pslot = P->pcg_pslot.p;
+    ps.bstart = P->pcg_bstart.p; ps.badj_off = P->pcg_badj_off.p; ps.badj = P->pcg_badj.p;
+    ps.whole = P->pcg_whole.p; ps.blk = P->pcg_blk.p; ps.bcomp = P->pcg_bcomp.p; ps.ncomp_blocks = P->pcg_ncb.p;
+    ps.Binv = P->pcg_Binv.p; ps.C0inv = P->pcg_C0inv.p;
+    P->have_pcg = true;
+    return TP_OK;
+}
+
 // Cotan sparsity pattern and connected components (host union-find on a copy of F).
 tp_status ensure_lap(tp_problem* P)
 {
@@ -306,9 +449,10 @@ tp_status ensure_lap(tp_problem* P)
     TP_TRY(P->lap_col.ensure(std::max<int64_t>(nnz, 1), s));
     TP_TRY(P->lap_val.ensure(std::max<int64_t>(nnz, 1), s));
     TP_HIP(launch_lap_pattern_fill(P->nV, P->vf_off.p, P->tmp_j.p, P->lap_off.p, P->lap_col.p, s));
+    std::vector<int32_t> hoff(P->nV + 1), hcol(std::max<int64_t>(nnz, 1));
     {
-        std::vector<int32_t> hoff(P->nV + 1);
         TP_HIP(hipMemcpyAsync(hoff.data(), P->lap_off.p, sizeof(int32_t) * (P->nV + 1), hipMemcpyDeviceToHost, s));
+        TP_HIP(hipMemcpyAsync(hcol.data(), P->lap_col.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToHost, s));
         TP_HIP(hipStreamSynchronize(s));
         int w = 1;
         for (int64_t v = 0; v < P->nV; ++v) w = std::max(w, hoff[v + 1] - hoff[v]);
@@ -353,6 +497,7 @@ tp_status ensure_lap(tp_problem* P)
     TP_HIP(hipMemcpyAsync(P->comp.p, label.data(), sizeof(int32_t) * P->nV, hipMemcpyHostToDevice, s));
     TP_HIP(hipMemcpyAsync(P->inv_count.p, cnt.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
     TP_HIP(hipStreamSynchronize(s));
+    if (P->prm.cg_precond) TP_TRY(build_pcg(P, label, nc, hoff, hcol));
     P->have_lap = true;
     return TP_OK;
 }
@@ -365,6 +510,7 @@ tp_status ensure_cotan(tp_problem* P)
                                    P->lap_col.p, P->lap_val.p, P->stream));
         TP_HIP(launch_csr_to_ell(P->nV, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->ell_w,
                                  P->ell_col.p, P->ell_val.p, P->stream));
+        if (P->have_pcg) TP_HIP(launch_pcg_setup(P->pcg, P->lap_off.p, P->lap_val.p, P->stream));
         P->cotan_valid = true;
     }
     return TP_OK;
@@ -482,11 +628,33 @@ tp_status run_cg(tp_problem* P, double* b, double* x, int k, int* it_max, double
     TP_TRY(ensure_cg(P, k));
     hipStream_t s = P->stream;
     TP_HIP(launch_project_mean(b, k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
-    CgWork w;
-    w.Z = P->cg_Z.p; w.p = P->cg_p.p; w.red = P->cg_red.p; w.bar = P->cg_bar.p;
-    w.iters = P->cg_iters.p; w.relres = P->cg_relres.p; w.flags = P->flags.p;
-    TP_HIP(launch_cg(P->nV, P->ell_col.p, P->ell_val.p, P->ell_w, b, x, k, P->prm.cg_rtol,
-                     P->prm.cg_maxiter, w, s));
+    if (P->have_pcg) {
+        // preconditioned solve in block order, up to kMaxGroupCols columns per launch
+        const int64_t n = P->nV;
+        const int kc_max = std::min(k, kMaxGroupCols);
+        TP_TRY(P->pcg_Vb.ensure((size_t)n * kc_max, s));
+        TP_TRY(P->pcg_rho.ensure((size_t)P->pcg.nb * kc_max, s));
+        TP_TRY(P->pcg_red.ensure((size_t)2 * P->pcg.nb * 2 * kc_max, s));
+        TP_TRY(P->pcg_bp.ensure((size_t)n * kc_max, s));
+        TP_TRY(P->pcg_xp.ensure((size_t)n * kc_max, s));
+        PcgWork pw;
+        pw.Vb = P->pcg_Vb.p; pw.rho = P->pcg_rho.p; pw.red = P->pcg_red.p;
+        pw.bar = P->cg_bar.p; pw.flags = P->flags.p;
+        for (int c0 = 0; c0 < k; c0 += kMaxGroupCols) {
+            const int kc = std::min(kMaxGroupCols, k - c0);
+            pw.iters = P->cg_iters.p + c0;
+            pw.relres = P->cg_relres.p + c0;
+            TP_HIP(launch_permute_rows(n, kc, P->pcg.perm, k, c0, b, P->pcg_bp.p, true, s));
+            TP_HIP(launch_pcg(P->pcg, P->pcg_bp.p, P->pcg_xp.p, kc, P->prm.cg_rtol, P->prm.cg_maxiter, pw, s));
+            TP_HIP(launch_permute_rows(n, kc, P->pcg.perm, k, c0, P->pcg_xp.p, x, false, s));
+        }
+    } else {
+        CgWork w;
+        w.Z = P->cg_Z.p; w.p = P->cg_p.p; w.red = P->cg_red.p; w.bar = P->cg_bar.p;
+        w.iters = P->cg_iters.p; w.relres = P->cg_relres.p; w.flags = P->flags.p;
+        TP_HIP(launch_cg(P->nV, P->ell_col.p, P->ell_val.p, P->ell_w, b, x, k, P->prm.cg_rtol,
+                         P->prm.cg_maxiter, w, s));
+    }
     TP_HIP(launch_project_mean(x, k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
     std::vector<int> its(k);
     std::vector<double> res(k);
@@ -843,6 +1011,7 @@ tp_status tp_params_default(tp_params* p)
     p->precision = TP_PREC_FP32_HILO;
     p->cg_rtol = 1e-10;
     p->cg_maxiter = 20000;
+    p->cg_precond = 1;
     return TP_OK;
 }
 
@@ -937,6 +1106,33 @@ tp_status tp_problem_precond_apply(tp_problem* P, const double* b, int k, double
     if (k < 1 || k > kMaxCols) return fail(TP_E_INVALID_ARGUMENT, "k must lie in [1, 64]");
     set_error("");
     return run_precond(P, b, k, x_out, report);
+}
+
+tp_status tp_problem_poisson_solve(tp_problem* P, const double* b, int k, double* x_out,
+                                   tp_solve_report* report)
+{
+    TP_TRY(bind(P));
+    if (!b || !x_out) return fail(TP_E_INVALID_ARGUMENT, "b and x_out must be non-NULL");
+    if (k < 1 || k > kMaxCols) return fail(TP_E_INVALID_ARGUMENT, "k must lie in [1, 64]");
+    set_error("");
+    TP_TRY(ensure_geometry(P));
+    TP_TRY(ensure_lap(P));
+    const size_t nk = (size_t)P->nV * k;
+    TP_TRY(P->W1.ensure(nk, P->stream));
+    TP_HIP(hipMemcpyAsync(P->W1.p, b, nk * sizeof(double), hipMemcpyDeviceToDevice, P->stream));
+    EventTimer tm(P->stream);
+    tm.mark(0);
+    int it = 0;
+    double res = 0;
+    tp_status st = run_cg(P, P->W1.p, x_out, k, &it, &res);
+    tm.mark(1);
+    if (report) {
+        std::memset(report, 0, sizeof(*report));
+        report->cg_iters[0] = it;
+        report->cg_relres[0] = res;
+        report->t_ms[0] = tm.ms(0, 1);
+    }
+    return st;
 }
 
 tp_status tp_precond_step(tp_problem* P, const tp_step_opts* opts, tp_step_report* report,

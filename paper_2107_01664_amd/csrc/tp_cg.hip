@@ -28,13 +28,8 @@
 namespace tp {
 
 constexpr int kCgBlock = 256;
-constexpr unsigned long long kSpinLimit = 1ull << 22;
 constexpr int kMaxW = 128;           // workgroups per column group
 constexpr int kMaxGroups = 8;
-constexpr int kLine = 32;            // unsigned words per 128-byte line
-// barrier words per group: 8 level-1 counters, 1 level-2 counter, 1 generation,
-// each on its own line
-constexpr int kBarWordsPerGroup = 10 * kLine;
 
 struct CgArgs {
     int64_t n;
@@ -57,59 +52,6 @@ struct CgArgs {
     int W;
     int rows_per_thread;
 };
-
-// Two-level barrier among the W workgroups of a group: workgroup w first arrives at
-// counter (w % 8); the last of that set arrives at the group counter; the last of those
-// advances the generation word that everybody waits on.
-__device__ bool group_barrier(unsigned* gbar, int w, int W, int* flags)
-{
-    __shared__ int ok_sh;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int ok = 1;
-        unsigned* gen = gbar + 9 * kLine;
-        unsigned* top = gbar + 8 * kLine;
-        const int sub = w & 7;
-        const int nsub = (W + 7 - sub) / 8;           // members of this level-1 set
-        const int ntop = W < 8 ? W : 8;                 // non-empty level-1 sets
-        __threadfence();
-        const unsigned g = __hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned* c1 = gbar + sub * kLine;
-        const unsigned a1 = __hip_atomic_fetch_add(c1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        bool last = false;
-        if ((int)a1 + 1 == nsub) {
-            __hip_atomic_store(c1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned a2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if ((int)a2 + 1 == ntop) {
-                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                last = true;
-            }
-        }
-        if (!last) {
-            unsigned long long spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(1);
-                ++spins;
-                if (spins > kSpinLimit) {
-                    ok = 0;
-                    break;
-                }
-                if ((spins & 255ull) == 0ull &&
-                    __hip_atomic_load(&flags[kFlagCgAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ok = 0;
-                    break;
-                }
-            }
-            if (!ok) __hip_atomic_store(&flags[kFlagCgAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __threadfence();
-        if (__hip_atomic_load(&flags[kFlagCgAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-        ok_sh = ok;
-    }
-    __syncthreads();
-    return ok_sh != 0;
-}
 
 // Workgroup sums of two KG-vectors (fixed butterfly, then waves in order) into sh_out.
 template <int KG>
@@ -186,12 +128,8 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs A)
         }
     }
 
-    // ---- initial state: x0 = 0, r0 = b, w0 = C b, s_{-1} = p_{-1} = 0
-    double ga[KG], de[KG];
-#pragma unroll
-    for (int c = 0; c < KG; ++c) ga[c] = de[c] = 0.0;
-    for (int64_t i = rb + threadIdx.x; i < re; i += kCgBlock) {
-        double acc[KG];
+    // sparse row i of C applied to y (row stride k, columns c0..c0+nc) -> acc
+    auto spmv_row = [&](int64_t i, const double* y, int64_t ystride, double (&acc)[KG]) {
 #pragma unroll
         for (int c = 0; c < KG; ++c) acc[c] = 0.0;
         for (int e = 0; e < A.ell_w; ++e) {
@@ -199,121 +137,181 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs A)
             const double v = A.eval[(int64_t)e * n + i];
 #pragma unroll
             for (int c = 0; c < KG; ++c)
-                if (c < nc) acc[c] += v * A.b[j * k + c0 + c];
+                if (c < nc) acc[c] += v * y[j * ystride + c];
         }
-        double* zi = Z0 + i * zrow;
-#pragma unroll
-        for (int c = 0; c < KG; ++c) {
-            if (c < nc) {
-                const double bv = A.b[i * k + c0 + c];
-                A.x[i * k + c0 + c] = 0.0;
-                A.p[i * k + c0 + c] = 0.0;
-                zi[c0 + c] = bv;               // r
-                zi[k + c0 + c] = acc[c];       // w
-                zi[2 * k + c0 + c] = 0.0;      // s
-                ga[c] += bv * bv;
-                de[c] += acc[c] * bv;
-            }
-        }
-    }
-    block_sums2<KG>(ga, de, sh_wave, sh_sum);
-    if (threadIdx.x < 2 * KG) redg[(0 * A.W + w) * 2 * KG + threadIdx.x] = sh_sum[threadIdx.x];
-    if (!group_barrier(gbar, w, A.W, A.flags)) return;
-    group_sum(redg);
+    };
 
-    double gam[KG], bb[KG], alpha[KG], beta[KG];
+    double gam[KG], bb[KG], rr[KG], alpha[KG], beta[KG];
     bool done[KG];
     int its[KG];
 #pragma unroll
     for (int c = 0; c < KG; ++c) {
-        gam[c] = sh_grp[c];
-        const double d0 = sh_grp[KG + c];
-        bb[c] = gam[c];
-        beta[c] = 0.0;
-        done[c] = (c >= nc) || !(bb[c] > 0.0);
-        alpha[c] = done[c] ? 0.0 : gam[c] / d0;
+        done[c] = (c >= nc);
         its[c] = 0;
+        bb[c] = rr[c] = 0.0;
     }
-    __syncthreads();
-
-    for (int it = 0; it < A.maxiter; ++it) {
-        bool all = true;
+    int total_it = 0;
+    // Partial sums for the m-th barrier go to buffer m % 2: a buffer is rewritten only
+    // after the next barrier, by which time every reader of it has arrived there.
+    int bcount = 0;
+    auto redbuf = [&]() { return redg + (int64_t)(bcount & 1) * A.W * 2 * KG; };
+    constexpr int kMaxRestarts = 6;
+    for (int cycle = 0; cycle <= kMaxRestarts; ++cycle) {
+        // ---- R: r = b - C x (x = 0 on the first cycle), s = 0, p = 0; sums of r^2
+        double loc[KG], dum[KG];
 #pragma unroll
-        for (int c = 0; c < KG; ++c) all = all && done[c];
-        if (all) break;
-        const double* Zc = (it & 1) ? Z1 : Z0;
-        double* Zn = (it & 1) ? Z0 : Z1;
-#pragma unroll
-        for (int c = 0; c < KG; ++c) ga[c] = de[c] = 0.0;
+        for (int c = 0; c < KG; ++c) loc[c] = dum[c] = 0.0;
         for (int64_t i = rb + threadIdx.x; i < re; i += kCgBlock) {
-            // w_{i+1} = C r_{i+1}, with r_{i+1}(j) = r_i(j) - alpha (w_i(j) + beta s_{i-1}(j))
-            double acc[KG];
+            double cx[KG];
+            if (cycle == 0) {
 #pragma unroll
-            for (int c = 0; c < KG; ++c) acc[c] = 0.0;
-            auto add_entry = [&](int64_t j, double v) {
-                const double* zj = Zc + j * zrow + c0;
-#pragma unroll
-                for (int c = 0; c < KG; ++c)
-                    if (c < nc) acc[c] += v * (zj[c] - alpha[c] * (zj[k + c] + beta[c] * zj[2 * k + c]));
-            };
-            int e0 = 0;
-            if (cached) {
-#pragma unroll
-                for (int e = 0; e < kCache; ++e)
-                    if (e < A.ell_w) add_entry(cj[e], cv[e]);
-                e0 = kCache;
+                for (int c = 0; c < KG; ++c) cx[c] = 0.0;
+            } else {
+                spmv_row(i, A.x + c0, k, cx);
             }
-            for (int e = e0; e < A.ell_w; ++e)
-                add_entry(A.ecol[(int64_t)e * n + i], A.eval[(int64_t)e * n + i]);
-            const double* zi = Zc + i * zrow + c0;
-            double* zo = Zn + i * zrow + c0;
+            double* zi = Z0 + i * zrow;
 #pragma unroll
             for (int c = 0; c < KG; ++c) {
                 if (c < nc) {
                     const int64_t id = i * k + c0 + c;
-                    const double r = zi[c], wv = zi[k + c], s = zi[2 * k + c];
-                    const double pn = r + beta[c] * A.p[id];
-                    const double sn = wv + beta[c] * s;
-                    A.p[id] = pn;
-                    A.x[id] += alpha[c] * pn;
-                    const double rn = r - alpha[c] * sn;
-                    zo[c] = rn;
-                    zo[k + c] = acc[c];
-                    zo[2 * k + c] = sn;
-                    ga[c] += rn * rn;
-                    de[c] += acc[c] * rn;
+                    if (cycle == 0) A.x[id] = 0.0;
+                    const double rv = A.b[id] - cx[c];
+                    A.p[id] = 0.0;
+                    zi[c0 + c] = rv;
+                    zi[2 * k + c0 + c] = 0.0;
+                    loc[c] += rv * rv;
+                }
+            }
+        }
+        block_sums2<KG>(loc, dum, sh_wave, sh_sum);
+        if (threadIdx.x < 2 * KG) redbuf()[w * 2 * KG + threadIdx.x] = sh_sum[threadIdx.x];
+        if (!group_barrier(gbar, w, A.W, A.flags)) return;
+        group_sum(redbuf());
+        ++bcount;
+        bool all = true;
+#pragma unroll
+        for (int c = 0; c < KG; ++c) {
+            rr[c] = sh_grp[c];
+            if (cycle == 0) {
+                bb[c] = rr[c];
+                if (!(bb[c] > 0.0)) done[c] = true;
+            }
+            if (!done[c] && sqrt(rr[c] / bb[c]) <= A.rtol) done[c] = true;
+            all = all && done[c];
+        }
+        __syncthreads();
+        if (all || total_it >= A.maxiter) break;
+
+        // ---- W: w = C r; gamma = (r, r), delta = (w, r)
+        double ga[KG], de[KG];
+#pragma unroll
+        for (int c = 0; c < KG; ++c) ga[c] = de[c] = 0.0;
+        for (int64_t i = rb + threadIdx.x; i < re; i += kCgBlock) {
+            double acc[KG];
+            spmv_row(i, Z0 + c0, zrow, acc);
+            double* zi = Z0 + i * zrow;
+#pragma unroll
+            for (int c = 0; c < KG; ++c) {
+                if (c < nc) {
+                    const double rv = zi[c0 + c];
+                    zi[k + c0 + c] = acc[c];
+                    ga[c] += rv * rv;
+                    de[c] += acc[c] * rv;
                 }
             }
         }
         block_sums2<KG>(ga, de, sh_wave, sh_sum);
-        double* red = redg + (int64_t)((it + 1) & 1) * A.W * 2 * KG;
-        if (threadIdx.x < 2 * KG) red[w * 2 * KG + threadIdx.x] = sh_sum[threadIdx.x];
+        if (threadIdx.x < 2 * KG) redbuf()[w * 2 * KG + threadIdx.x] = sh_sum[threadIdx.x];
         if (!group_barrier(gbar, w, A.W, A.flags)) return;
-        group_sum(red);
+        group_sum(redbuf());
+        ++bcount;
 #pragma unroll
         for (int c = 0; c < KG; ++c) {
-            if (!done[c]) {
-                const double gn = sh_grp[c], dn = sh_grp[KG + c];
-                its[c] = it + 1;
-                const double bn = gn / gam[c];
-                const double an = gn / (dn - bn * gn / alpha[c]);
-                gam[c] = gn;
-                if (sqrt(gn / bb[c]) <= A.rtol) {
-                    done[c] = true;
-                    alpha[c] = 0.0;
-                    beta[c] = 0.0;
-                } else {
-                    beta[c] = bn;
-                    alpha[c] = an;
-                }
-            }
+            gam[c] = sh_grp[c];
+            beta[c] = 0.0;
+            alpha[c] = done[c] ? 0.0 : gam[c] / sh_grp[KG + c];
         }
         __syncthreads();
+
+        // ---- iterations until every open column meets rtol on the recursive residual
+        for (int it = 0; total_it < A.maxiter; ++it) {
+            ++total_it;
+            const double* Zc = (it & 1) ? Z1 : Z0;
+            double* Zn = (it & 1) ? Z0 : Z1;
+#pragma unroll
+            for (int c = 0; c < KG; ++c) ga[c] = de[c] = 0.0;
+            for (int64_t i = rb + threadIdx.x; i < re; i += kCgBlock) {
+                // w_{i+1} = C r_{i+1}, r_{i+1}(j) = r_i(j) - alpha (w_i(j) + beta s_{i-1}(j))
+                double acc[KG];
+#pragma unroll
+                for (int c = 0; c < KG; ++c) acc[c] = 0.0;
+                auto add_entry = [&](int64_t j, double v) {
+                    const double* zj = Zc + j * zrow + c0;
+#pragma unroll
+                    for (int c = 0; c < KG; ++c)
+                        if (c < nc) acc[c] += v * (zj[c] - alpha[c] * (zj[k + c] + beta[c] * zj[2 * k + c]));
+                };
+                int e0 = 0;
+                if (cached) {
+#pragma unroll
+                    for (int e = 0; e < kCache; ++e)
+                        if (e < A.ell_w) add_entry(cj[e], cv[e]);
+                    e0 = kCache;
+                }
+                for (int e = e0; e < A.ell_w; ++e)
+                    add_entry(A.ecol[(int64_t)e * n + i], A.eval[(int64_t)e * n + i]);
+                const double* zi = Zc + i * zrow + c0;
+                double* zo = Zn + i * zrow + c0;
+#pragma unroll
+                for (int c = 0; c < KG; ++c) {
+                    if (c < nc) {
+                        const int64_t id = i * k + c0 + c;
+                        const double rv = zi[c], wv = zi[k + c], sv = zi[2 * k + c];
+                        const double pn = rv + beta[c] * A.p[id];
+                        const double sn = wv + beta[c] * sv;
+                        A.p[id] = pn;
+                        A.x[id] += alpha[c] * pn;
+                        const double rn = rv - alpha[c] * sn;
+                        zo[c] = rn;
+                        zo[k + c] = acc[c];
+                        zo[2 * k + c] = sn;
+                        ga[c] += rn * rn;
+                        de[c] += acc[c] * rn;
+                    }
+                }
+            }
+            block_sums2<KG>(ga, de, sh_wave, sh_sum);
+            if (threadIdx.x < 2 * KG) redbuf()[w * 2 * KG + threadIdx.x] = sh_sum[threadIdx.x];
+            if (!group_barrier(gbar, w, A.W, A.flags)) return;
+            group_sum(redbuf());
+            ++bcount;
+            bool conv = true;
+#pragma unroll
+            for (int c = 0; c < KG; ++c) {
+                if (!done[c] && alpha[c] != 0.0) {
+                    const double gn = sh_grp[c], dn = sh_grp[KG + c];
+                    its[c] = total_it;
+                    rr[c] = gn;
+                    if (sqrt(gn / bb[c]) <= A.rtol) {
+                        alpha[c] = beta[c] = 0.0;       // frozen until verified
+                    } else {
+                        const double bn = gn / gam[c];
+                        alpha[c] = gn / (dn - bn * gn / alpha[c]);
+                        beta[c] = bn;
+                        gam[c] = gn;
+                        conv = false;
+                    }
+                }
+            }
+            __syncthreads();
+            if (conv) break;
+        }
+        // the next cycle's R phase recomputes the true residual from x
     }
     if (w == 0 && threadIdx.x < nc) {
         const int c = threadIdx.x;
         A.iters[c0 + c] = its[c];
-        A.relres[c0 + c] = bb[c] > 0.0 ? sqrt(gam[c] / bb[c]) : 0.0;
+        A.relres[c0 + c] = bb[c] > 0.0 ? sqrt(rr[c] / bb[c]) : 0.0;
     }
 }
 

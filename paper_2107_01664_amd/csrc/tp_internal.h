@@ -179,4 +179,134 @@ hipError_t launch_cg(int64_t n, const int32_t* ecol, const double* eval, int ell
                      const double* b, double* x, int k, double rtol, int maxiter,
                      const CgWork& w, hipStream_t s);
 
+// Two-level additive Schwarz preconditioned CG (blocks of pcg_block_size() vertices in
+// (component, Morton) order, dense block inverses in LDS, Galerkin coarse correction).
+struct PcgSetup {
+    int64_t n = 0;
+    int nb = 0;
+    int ell_w = 0;
+    const int32_t* perm = nullptr;        // [n] block order -> vertex
+    const int32_t* pcol = nullptr;        // [ell_w][n] permuted ELL columns
+    double* pval = nullptr;               // [ell_w][n] permuted ELL values (per geometry)
+    const uint8_t* pslot = nullptr;       // [ell_w][n]
+    const int32_t* bstart = nullptr;      // [nb + 1]
+    const int32_t* badj_off = nullptr;    // [nb + 1]
+    const int32_t* badj = nullptr;
+    const int32_t* whole = nullptr;       // [nb] block is a whole component
+    const int32_t* blk = nullptr;         // [n] block of each (permuted) row
+    const int32_t* bcomp = nullptr;       // [nb] component of each block
+    const int32_t* ncomp_blocks = nullptr;// [ncomp] blocks per component
+    float* Binv = nullptr;                // [nb][bs][bs], FP32
+    double* C0inv = nullptr;              // [nb][nb]
+};
+struct PcgWork {
+    double* Vb = nullptr;       // n * k
+    double* rho = nullptr;      // nb * k
+    double* red = nullptr;      // 2 * nb * 2k
+    unsigned* bar = nullptr;
+    int* iters = nullptr;
+    double* relres = nullptr;
+    int* flags = nullptr;
+};
+int pcg_block_size();
+int pcg_max_neighbors();
+bool pcg_supported(int64_t nb, int ncomp_blocks_max);
+hipError_t launch_pcg_setup(const PcgSetup& ps, const int32_t* lap_off, const double* lap_val, hipStream_t s);
+hipError_t launch_permute_rows(int64_t n, int k, const int32_t* perm, int ld, int c0, const double* src,
+                               double* dst, bool forward, hipStream_t s);
+hipError_t launch_pcg(const PcgSetup& ps, const double* b, double* x, int k, double rtol, int maxiter,
+                      const PcgWork& w, hipStream_t s);
+
+// ------------------------------------------------------------------ device-side sync
+
+constexpr unsigned long long kSpinLimit = 1ull << 22;
+constexpr int kLine = 32;            // unsigned words per 128-byte line
+// barrier words of one group: 8 level-1 counters, 1 level-2 counter, 1 generation,
+// each on its own line
+constexpr int kBarWordsPerGroup = 10 * kLine;
+
+#if defined(__HIPCC__)
+// Sum of a double over the 64 lanes of a wave in a fixed order, returned uniformly:
+// DPP quad swaps, half-row and row mirrors give each 16-lane row its sum in every lane
+// (each step adds the same two values in every lane of a pair, so all lanes agree), then
+// the four row sums are read and added as (r0 + r1) + (r2 + r3).
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double read_lane(double v, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wave_sum(double v)
+{
+    v = v + dpp_move<0xB1>(v);    // quad_perm [1,0,3,2]
+    v = v + dpp_move<0x4E>(v);    // quad_perm [2,3,0,1]
+    v = v + dpp_move<0x141>(v);   // row_half_mirror
+    v = v + dpp_move<0x140>(v);   // row_mirror
+    return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
+}
+
+// Two-level barrier among the W workgroups of a group: workgroup w first arrives at
+// counter (w % 8); the last of that set arrives at the group counter; the last of those
+// advances the generation word that everybody waits on.
+__device__ __forceinline__ bool group_barrier(unsigned* gbar, int w, int W, int* flags)
+{
+    // Every wave's stores are complete before the workgroup barrier; thread 0's agent-scope
+    // acquire-release arrival then publishes them and the acquire fence after the wait
+    // makes the other workgroups' stores visible to the whole workgroup.
+    __shared__ int ok_sh;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        unsigned* gen = gbar + 9 * kLine;
+        unsigned* top = gbar + 8 * kLine;
+        const int sub = w & 7;
+        const int nsub = (W + 7 - sub) / 8;           // members of this level-1 set
+        const int ntop = W < 8 ? W : 8;                 // non-empty level-1 sets
+        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        unsigned* c1 = gbar + sub * kLine;
+        const unsigned a1 = __hip_atomic_fetch_add(c1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        bool last = false;
+        if ((int)a1 + 1 == nsub) {
+            __hip_atomic_store(c1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned a2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            if ((int)a2 + 1 == ntop) {
+                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                last = true;
+            }
+        }
+        if (!last) {
+            unsigned long long spins = 0;
+            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                __builtin_amdgcn_s_sleep(1);
+                ++spins;
+                if (spins > kSpinLimit) {
+                    ok = 0;
+                    break;
+                }
+                if ((spins & 255ull) == 0ull &&
+                    __hip_atomic_load(&flags[kFlagCgAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+            }
+            if (!ok) __hip_atomic_store(&flags[kFlagCgAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (__hip_atomic_load(&flags[kFlagCgAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        ok_sh = ok;
+    }
+    __syncthreads();
+    return ok_sh != 0;
+}
+
+#endif
+
 }  // namespace tp

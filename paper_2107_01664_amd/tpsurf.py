@@ -34,6 +34,7 @@ EXPORTED = [
     "tp_problem_get_vertices", "tp_problem_energy", "tp_problem_gradient",
     "tp_problem_fractional_apply", "tp_problem_precond_apply", "tp_step_opts_default",
     "tp_precond_step", "tp_last_error", "tp_profile_enable", "tp_profile_reset", "tp_profile_get",
+    "tp_problem_poisson_solve",
 ]
 
 
@@ -45,7 +46,8 @@ class TpError(RuntimeError):
 
 class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("sigma", ctypes.c_double),
-                ("precision", ctypes.c_int), ("cg_rtol", ctypes.c_double), ("cg_maxiter", ctypes.c_int)]
+                ("precision", ctypes.c_int), ("cg_rtol", ctypes.c_double), ("cg_maxiter", ctypes.c_int),
+                ("cg_precond", ctypes.c_int)]
 
 
 class SolveReport(ctypes.Structure):
@@ -108,6 +110,7 @@ def lib() -> ctypes.CDLL:
         "tp_problem_gradient": [vp, P(d), vp],
         "tp_problem_fractional_apply": [vp, vp, i32, vp],
         "tp_problem_precond_apply": [vp, vp, i32, vp, P(SolveReport)],
+        "tp_problem_poisson_solve": [vp, vp, i32, vp, P(SolveReport)],
         "tp_step_opts_default": [P(StepOpts)],
         "tp_precond_step": [vp, P(StepOpts), P(StepReport), vp],
         "tp_profile_enable": [i32],
@@ -294,6 +297,17 @@ class Problem:
         rep = SolveReport()
         allow = (5,) if allow_not_converged else ()
         _check(lib().tp_problem_precond_apply(self._h, b.data_ptr(), b.shape[1], x.data_ptr(),
+                                              ctypes.byref(rep)), allow)
+        return (x[:, 0] if squeeze else x), rep
+
+    def poisson_solve(self, b, out=None, allow_not_converged=False):
+        """Per-component mean-zero solution of C x = P b (FP64 CG)."""
+        squeeze = b.dim() == 1
+        b = _cols(b, self.nV, "b")
+        x = out if out is not None else torch.empty_like(b)
+        rep = SolveReport()
+        allow = (5,) if allow_not_converged else ()
+        _check(lib().tp_problem_poisson_solve(self._h, b.data_ptr(), b.shape[1], x.data_ptr(),
                                               ctypes.byref(rep)), allow)
         return (x[:, 0] if squeeze else x), rep
 
