@@ -8,7 +8,10 @@ One step on the 40,000-face noisy torus (R = 1, r = 0.3, 200 x 100 grid, vertex 
      all-pairs fractional apply on 3 columns.
 value = ordered face-pair interactions per second over the whole step (3 F (F - 1) per step).
 
-Prints ONE JSON line (rank 0).  `--gpus N` with N > 1 exits: this build runs on one GPU.
+Prints ONE JSON line (rank 0).  `--gpus N` with N > 1 exits: the path runs on one GPU.
+
+`--copy-probe` instead runs a plain device-to-device copy of known size; its FETCH_SIZE
+and WRITE_SIZE counter readings calibrate those counters for the traffic figure.
 """
 from __future__ import annotations
 
@@ -42,7 +45,24 @@ def parse():
     ap.add_argument("--precision", type=int, default=0, help="0 fp32 hi/lo, 1 fp32, 2 fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain 256 MiB device copy 5 times (counter calibration)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A copy of known size: 256 MiB read and 256 MiB written per launch."""
+    import torch
+
+    n = 64 << 20
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                      "launches": 5}), flush=True)
 
 
 def cpu_baseline(mesh, u, target_s: float):
@@ -92,8 +112,8 @@ def cpu_baseline(mesh, u, target_s: float):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {a.gpus} is not supported "
-              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the path runs on one GPU; --gpus {a.gpus} is not supported",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -104,6 +124,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if a.copy_probe:
+        copy_probe()
+        return
     tp.lib()
     dev = torch.device("cuda", 0)
     mesh = mg.workload("torus40k")
