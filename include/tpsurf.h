@@ -184,8 +184,11 @@ typedef struct {
     double phi_before[2];    /* constraint values Phi(f) (area, volume; unused rows 0)   */
     double phi_trial[2];     /* Phi(f + tau x)                                           */
     double phi_after[2];     /* Phi after the corrective step                            */
-    double t_ms[8];          /* gradient, constraints, preconditioner, Schur, line search,
-                                projection, total, (unused)                               */
+    double t_ms[8];          /* device ms: [0] dE and right-hand sides, [1] first Poisson
+                                solve, [2] preconditioner (both solves and the fractional
+                                apply), [3] Schur system and direction, [4] line search,
+                                [5] corrective projection and new energy, [6] whole step;
+                                [7] number of problems whose launches this step shared    */
 } tp_step_report;
 
 /* One projected, preconditioned descent step (Sec. 3 steps 1-5 with Sec. 5.3-5.4):
@@ -196,6 +199,30 @@ typedef struct {
  * report may be NULL. */
 TP_API tp_status tp_precond_step(tp_problem* prob, const tp_step_opts* opts, tp_step_report* report,
                           double* direction_out);
+
+/* Descent steps of n problems in one call (continuous batching of steps, not in the
+ * paper): every phase of the step above runs for all problems before the next, the
+ * all-pairs work of a phase in shared launches and the Poisson solves in shared
+ * cooperative launches.  Each problem's arithmetic is that of tp_precond_step on it alone,
+ * so its vertices and report are bit-identical to a step taken alone.  The problems must
+ * be distinct and created on the same device and stream; problems that differ in
+ * precision, exponents, sigma or number of active constraints run as separate groups.
+ * opts: n entries or NULL (defaults); reports, statuses: n entries or NULL.  Returns TP_OK
+ * when every problem succeeded, else the first problem's failure (statuses has all). */
+TP_API tp_status tp_batch_step(tp_problem* const* probs, int n, const tp_step_opts* opts,
+                               tp_step_report* reports, tp_status* statuses);
+
+/* Device memory (bytes) the problem currently holds (its resident state and work arrays;
+ * grows on first use of each call). */
+TP_API tp_status tp_problem_device_bytes(const tp_problem* prob, uint64_t* bytes);
+
+/* Upper bound of the device memory a problem with nV vertices, nF faces, largest vertex
+ * degree max_degree and ncomp connected components holds after descent steps with
+ * n_constraints (0..2) active constraint rows, for admission against a memory budget.
+ * Uses the current device's pair-kernel plans. */
+TP_API tp_status tp_estimate_device_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp,
+                                          const tp_params* params, int n_constraints,
+                                          uint64_t* bytes);
 
 /* ------------------------------------------------------------------- diagnostics */
 

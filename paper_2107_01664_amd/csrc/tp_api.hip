@@ -111,6 +111,7 @@ struct DevBuf {
         p = nullptr;
         n = 0;
     }
+    size_t bytes() const { return n * sizeof(T); }
     // Grow to at least cnt elements (contents are not preserved).
     tp_status ensure(size_t cnt, hipStream_t s)
     {
@@ -127,6 +128,70 @@ struct DevBuf {
         }
         n = want;
         return TP_OK;
+    }
+};
+
+// Pinned host memory (hipHostMalloc), for scalars read back after a stream sync.
+template <class T>
+struct HostBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf&) = delete;
+    HostBuf& operator=(const HostBuf&) = delete;
+    ~HostBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    // Grow to at least cnt elements (zeroed); the caller makes sure no copy still uses it.
+    tp_status ensure(size_t cnt)
+    {
+        if (cnt <= n && p) return TP_OK;
+        release();
+        const size_t want = std::max<size_t>(cnt, 1);
+        if (hipHostMalloc((void**)&p, want * sizeof(T), hipHostMallocDefault) != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            return fail(TP_E_OUT_OF_MEMORY, "hipHostMalloc of " + std::to_string(want * sizeof(T)) + " bytes failed");
+        }
+        std::memset((void*)p, 0, want * sizeof(T));
+        n = want;
+        return TP_OK;
+    }
+};
+
+// Slots of the per-problem device scalars (P->scal) and their pinned mirror (P->hs).
+enum ScalarSlot {
+    kSlotE = 0,       // energy (twice the energy after a gradient)
+    kSlotArea = 1,
+    kSlotVol6 = 2,    // six times the signed volume
+    kSlotMax = 3,     // largest vertex displacement of the direction
+    kSlotGG = 4,      // g.g per coordinate (3)
+    kSlotGX = 7,      // g.x per coordinate (3)
+    kSlotS = 10,      // J Y, 2 x 2 entries of 3 coordinates each (12)
+    kSlotR = 22,      // J y_g, 2 entries of 3 (6)
+    kNumSlots = 28
+};
+
+// Ring of device tables for the multi-problem CG launches and their pinned staging.
+constexpr int kTabSlots = 4;
+struct TabRing {
+    DevBuf<char> dev;
+    HostBuf<char> host;
+    size_t slot_bytes = 0;
+    hipEvent_t ev[kTabSlots] = {nullptr, nullptr, nullptr, nullptr};
+    bool used[kTabSlots] = {false, false, false, false};
+    int next = 0;
+    TabRing() = default;
+    TabRing(const TabRing&) = delete;
+    TabRing& operator=(const TabRing&) = delete;
+    ~TabRing()
+    {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -181,6 +246,32 @@ struct tp_problem {
     DevBuf<unsigned> cg_bar;
     DevBuf<int> cg_iters;
     DevBuf<double> R, Y, W1, W2, gbuf, dir, Vt, Vsave;
+
+    // pinned host mirrors of device scalars, flags and CG results; multi-problem CG tables
+    HostBuf<double> hs, hrelres;
+    HostBuf<int> hflags, hiters;
+    TabRing tab;
+
+    // device memory held by the problem
+    size_t device_bytes() const
+    {
+        size_t b = V.bytes() + F.bytes() + fx.bytes() + fl.bytes() + fn.bytes() + dx.bytes() + dn.bytes() +
+                   flags.bytes();
+        b += vf_off.bytes() + vf_idx.bytes() + tmp_i.bytes() + tmp_j.bytes() + lap_off.bytes() +
+             lap_col.bytes() + comp.bytes() + lap_val.bytes() + inv_count.bytes() + ell_col.bytes() +
+             ell_val.bytes();
+        b += pcg_perm.bytes() + pcg_pcol.bytes() + pcg_bstart.bytes() + pcg_badj_off.bytes() +
+             pcg_badj.bytes() + pcg_whole.bytes() + pcg_blk.bytes() + pcg_bcomp.bytes() + pcg_ncb.bytes() +
+             pcg_pslot.bytes() + pcg_Binv.bytes() + pcg_pval.bytes() + pcg_C0inv.bytes() + pcg_Vb.bytes() +
+             pcg_rho.bytes() + pcg_red.bytes() + pcg_bp.bytes() + pcg_xp.bytes();
+        b += part.bytes() + gface.bytes() + zbuf.bytes() + scal.bytes() + red.bytes() + vol6.bytes() +
+             edge.bytes() + ub.bytes();
+        b += cg_Z.bytes() + cg_p.bytes() + cg_red.bytes() + cg_relres.bytes() + cg_bar.bytes() +
+             cg_iters.bytes();
+        b += R.bytes() + Y.bytes() + W1.bytes() + W2.bytes() + gbuf.bytes() + dir.bytes() + Vt.bytes() +
+             Vsave.bytes() + tab.dev.bytes();
+        return b;
+    }
 };
 
 namespace {
@@ -263,6 +354,10 @@ tp_status alloc_faces(tp_problem* P)
     TP_HIP(hipMemsetAsync(P->flags.p, 0, sizeof(int) * kNumFlags, P->stream));
     TP_TRY(P->scal.ensure(256, P->stream));
     TP_TRY(P->red.ensure(reduce_scratch_doubles(16), P->stream));
+    TP_TRY(P->hs.ensure(256));
+    TP_TRY(P->hflags.ensure(kNumFlags));
+    TP_TRY(P->hiters.ensure(2 * kMaxCols));
+    TP_TRY(P->hrelres.ensure(2 * kMaxCols));
     return TP_OK;
 }
 
@@ -536,77 +631,166 @@ tp_status total_area_volume(tp_problem* P, const double* Vsrc, double* area, dou
     return TP_OK;
 }
 
-// ------------------------------------------------------------------ energy / gradient
+// ------------------------------------------------------------------ batches
+//
+// A batch is a list of problems that share a device and a stream.  The all-pairs work of
+// one phase of all its problems goes into shared launches (launch_pairs_*), and their CG
+// solves into shared cooperative launches (launch_pcg_batch); the O(F) and O(V) passes are
+// launched per problem back to back, and the host waits once per phase for the whole
+// batch.  A problem's arithmetic does not depend on the other problems of its batch, so
+// its results are the same alone and in any batch.
+
+using Batch = std::vector<tp_problem*>;
 
 bool finite(double x) { return std::isfinite(x); }
 
-tp_status run_energy(tp_problem* P, double* E)
+// Copy the device scalars and flags of every problem to its pinned host mirrors.
+tp_status enqueue_fetch(const Batch& B)
 {
-    const PairPlan pl = plan_for(kKindEnergy, P->prm.precision, 1, P->nF, P->cap);
-    TP_TRY(P->part.ensure((size_t)pl.n_split * pl.irows, P->stream));
-    TP_TRY(P->gface.ensure((size_t)pl.irows, P->stream));
-    {
-        PairTimer t(kKindEnergy, (double)P->nF * (double)(P->nF - 1), 0.0, P->stream);
-        TP_HIP(launch_pairs_energy(P->fd, pl, P->prm.precision, P->prm.alpha, P->prm.beta, P->part.p, P->stream));
-        t.stop();
+    for (tp_problem* P : B) {
+        TP_HIP(hipMemcpyAsync(P->hs.p, P->scal.p, sizeof(double) * kNumSlots, hipMemcpyDeviceToHost, P->stream));
+        TP_HIP(hipMemcpyAsync(P->hflags.p, P->flags.p, sizeof(int) * kNumFlags, hipMemcpyDeviceToHost, P->stream));
     }
-    TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, 1, pl.irows, P->nF, P->gface.p, pl.irows, P->stream));
-    // E = sum_S a_S sum_T a_T K(S,T)
-    TP_HIP(launch_dot_cols(&P->dx.p[0].w, 4, P->gface.p, 1, P->nF, 1, P->red.p, P->scal.p, P->stream));
-    TP_TRY(read_scalars(P, P->scal.p, E, 1));
-    if (!finite(*E)) return fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
     return TP_OK;
 }
 
-tp_status run_gradient(tp_problem* P, double* E, double* dE)
+tp_status sync_batch(const Batch& B)
 {
-    TP_TRY(ensure_vf(P));
-    const PairPlan pl = plan_for(kKindGrad, P->prm.precision, 1, P->nF, P->cap);
-    TP_TRY(P->part.ensure((size_t)pl.n_split * 7 * pl.irows, P->stream));
-    TP_TRY(P->gface.ensure((size_t)7 * pl.irows, P->stream));
-    {
-        PairTimer t(kKindGrad, (double)P->nF * (double)(P->nF - 1), 0.0, P->stream);
-        TP_HIP(launch_pairs_grad(P->fd, pl, P->prm.precision, P->prm.alpha, P->prm.beta, P->part.p, P->stream));
-        t.stop();
-    }
-    TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, 7, pl.irows, P->nF, P->gface.p, pl.irows, P->stream));
-    TP_HIP(launch_grad_gather(P->V.p, P->F.p, P->nV, P->nF, P->vf_off.p, P->vf_idx.p, P->gface.p, pl.irows, dE, P->stream));
-    // E = (1/2) sum_S a_S dE/da_S, since dE/da_S = sum_T a_T (K(S,T) + K(T,S))
-    TP_HIP(launch_dot_cols(&P->dx.p[0].w, 4, P->gface.p + 6 * pl.irows, 1, P->nF, 1, P->red.p, P->scal.p, P->stream));
-    double twoE = 0;
-    TP_TRY(read_scalars(P, P->scal.p, &twoE, 1));
-    *E = 0.5 * twoE;
-    if (!finite(*E)) return fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
+    TP_HIP(hipStreamSynchronize(B[0]->stream));
     return TP_OK;
 }
 
-// Lu[:, c] for columns of u (row stride ldu) into Lu (row stride ldl), k columns.
-tp_status run_fractional(tp_problem* P, const double* u, int ldu, int k, double* Lu, int ldl)
+// Status from the fetched device flags of P (clears them on both sides).
+tp_status flag_status(tp_problem* P)
 {
-    TP_TRY(ensure_vf(P));
-    const int prec = P->prm.precision;
+    int* h = P->hflags.p;
+    const int bad = h[kFlagBadIndex], nonfin = h[kFlagNonFinite], degen = h[kFlagDegenerate],
+              abort_ = h[kFlagCgAbort];
+    if (bad | nonfin | degen | abort_) {
+        TP_HIP(hipMemsetAsync(P->flags.p, 0, sizeof(int) * kNumFlags, P->stream));
+        for (int q = 0; q < kNumFlags; ++q) h[q] = 0;
+    }
+    if (bad) return fail(TP_E_BAD_INDEX, "a face refers to a vertex index outside [0, nV)");
+    if (nonfin) return fail(TP_E_NONFINITE, "non-finite vertex coordinates or face quantities");
+    if (degen) return fail(TP_E_DEGENERATE_FACE, "a face has zero area (its normal is undefined)");
+    if (abort_) return fail(TP_E_DEVICE, "CG workgroup barrier timed out");
+    return TP_OK;
+}
+
+// ------------------------------------------------------------------ all-pairs phases
+
+// E of every problem (face data must describe the point of evaluation) -> scal[slot].
+tp_status enqueue_energy(const Batch& B, int slot)
+{
+    if (B.empty()) return TP_OK;
+    hipStream_t s = B[0]->stream;
+    const int prec = B[0]->prm.precision;
+    std::vector<PairJob> jobs;
+    std::vector<PairPlan> plans;
+    double pairs = 0;
+    for (tp_problem* P : B) {
+        const PairPlan pl = plan_for(kKindEnergy, prec, 1, P->nF, P->cap);
+        TP_TRY(P->part.ensure((size_t)pl.n_split * pl.irows, s));
+        TP_TRY(P->gface.ensure((size_t)pl.irows, s));
+        jobs.push_back(make_pair_job(P->fd, pl, P->part.p));
+        plans.push_back(pl);
+        pairs += (double)P->nF * (double)(P->nF - 1);
+    }
+    {
+        PairTimer t(kKindEnergy, pairs, 0.0, s);
+        TP_HIP(launch_pairs_energy(jobs.data(), (int)jobs.size(), prec, B[0]->prm.alpha, B[0]->prm.beta, s));
+        t.stop();
+    }
+    for (size_t m = 0; m < B.size(); ++m) {
+        tp_problem* P = B[m];
+        const PairPlan& pl = plans[m];
+        TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, 1, pl.irows, P->nF, P->gface.p, pl.irows, s));
+        // E = sum_S a_S sum_T a_T K(S,T)
+        TP_HIP(launch_dot_cols(&P->dx.p[0].w, 4, P->gface.p, 1, P->nF, 1, P->red.p, P->scal.p + slot, s));
+    }
+    return TP_OK;
+}
+
+// dE of every problem into dE[m] (nV x 3) and 2E -> scal[slot].
+tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
+{
+    if (B.empty()) return TP_OK;
+    hipStream_t s = B[0]->stream;
+    const int prec = B[0]->prm.precision;
+    std::vector<PairJob> jobs;
+    std::vector<PairPlan> plans;
+    double pairs = 0;
+    for (tp_problem* P : B) {
+        TP_TRY(ensure_vf(P));
+        const PairPlan pl = plan_for(kKindGrad, prec, 1, P->nF, P->cap);
+        TP_TRY(P->part.ensure((size_t)pl.n_split * 7 * pl.irows, s));
+        TP_TRY(P->gface.ensure((size_t)7 * pl.irows, s));
+        jobs.push_back(make_pair_job(P->fd, pl, P->part.p));
+        plans.push_back(pl);
+        pairs += (double)P->nF * (double)(P->nF - 1);
+    }
+    {
+        PairTimer t(kKindGrad, pairs, 0.0, s);
+        TP_HIP(launch_pairs_grad(jobs.data(), (int)jobs.size(), prec, B[0]->prm.alpha, B[0]->prm.beta, s));
+        t.stop();
+    }
+    for (size_t m = 0; m < B.size(); ++m) {
+        tp_problem* P = B[m];
+        const PairPlan& pl = plans[m];
+        TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, 7, pl.irows, P->nF, P->gface.p, pl.irows, s));
+        TP_HIP(launch_grad_gather(P->V.p, P->F.p, P->nV, P->nF, P->vf_off.p, P->vf_idx.p, P->gface.p,
+                                  pl.irows, dE[m], s));
+        // 2E = sum_S a_S dE/da_S, since dE/da_S = sum_T a_T (K(S,T) + K(T,S))
+        TP_HIP(launch_dot_cols(&P->dx.p[0].w, 4, P->gface.p + 6 * pl.irows, 1, P->nF, 1, P->red.p,
+                               P->scal.p + slot, s));
+    }
+    return TP_OK;
+}
+
+// Lu[m][:, c] = (L^sigma u[m])[:, c] for k columns (row strides ldu, ldl).
+tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, int k, double* const* Lu,
+                             int ldl)
+{
+    if (B.empty()) return TP_OK;
+    hipStream_t s = B[0]->stream;
+    const int prec = B[0]->prm.precision;
     const size_t esz = prec == TP_PREC_FP64 ? sizeof(double) : sizeof(float);
+    for (tp_problem* P : B) TP_TRY(ensure_vf(P));
+    std::vector<PairJob> jobs(B.size());
+    std::vector<PairPlan> plans(B.size());
     for (int c0 = 0; c0 < k; c0 += kMaxGroupCols) {
         const int kc = std::min(kMaxGroupCols, k - c0);
         const int kp = (kc + 3) / 4 * 4;
-        const PairPlan pl = plan_for(kKindFrac, prec, kc, P->nF, P->cap);
-        TP_TRY(P->ub.ensure((size_t)P->cap * kp * esz, P->stream));
-        TP_TRY(P->part.ensure((size_t)pl.n_split * kc * pl.irows, P->stream));
-        TP_TRY(P->zbuf.ensure((size_t)kc * pl.irows, P->stream));
-        // face averages of columns [c0, c0 + kc): pass a shifted pointer with stride ldu
-        TP_HIP(launch_face_avg(P->F.p, P->nF, P->cap, u + c0, ldu, kc, kp, prec, P->ub.p, P->stream));
+        double pairs = 0;
+        for (size_t m = 0; m < B.size(); ++m) {
+            tp_problem* P = B[m];
+            const PairPlan pl = plan_for(kKindFrac, prec, kc, P->nF, P->cap);
+            TP_TRY(P->ub.ensure((size_t)P->cap * kp * esz, s));
+            TP_TRY(P->part.ensure((size_t)pl.n_split * kc * pl.irows, s));
+            TP_TRY(P->zbuf.ensure((size_t)kc * pl.irows, s));
+            // face averages of columns [c0, c0 + kc): a shifted pointer with stride ldu
+            TP_HIP(launch_face_avg(P->F.p, P->nF, P->cap, u[m] + c0, ldu, kc, kp, prec, P->ub.p, s));
+            jobs[m] = make_pair_job(P->fd, pl, P->part.p, P->ub.p);
+            plans[m] = pl;
+            pairs += (double)P->nF * (double)(P->nF - 1);
+        }
         {
-            PairTimer t(kKindFrac, (double)P->nF * (double)(P->nF - 1),
-                        (double)P->nF * (double)(P->nF - 1) * kc, P->stream);
-            TP_HIP(launch_pairs_frac(P->fd, pl, prec, P->sigma, P->ub.p, kc, kp, P->part.p, P->stream));
+            PairTimer t(kKindFrac, pairs, pairs * kc, s);
+            TP_HIP(launch_pairs_frac(jobs.data(), (int)jobs.size(), prec, B[0]->sigma, kc, s));
             t.stop();
         }
-        TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, kc, pl.irows, P->nF, P->zbuf.p, pl.irows, P->stream));
-        TP_HIP(launch_ut_gather(P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->fd, P->zbuf.p, pl.irows,
-                                kc, ldl, c0, Lu, P->stream));
+        for (size_t m = 0; m < B.size(); ++m) {
+            tp_problem* P = B[m];
+            const PairPlan& pl = plans[m];
+            TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, kc, pl.irows, P->nF, P->zbuf.p, pl.irows, s));
+            TP_HIP(launch_ut_gather(P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->fd, P->zbuf.p, pl.irows,
+                                    kc, ldl, c0, Lu[m], s));
+        }
     }
     return TP_OK;
 }
+
+// ------------------------------------------------------------------ Poisson solves
 
 tp_status ensure_cg(tp_problem* P, int k)
 {
@@ -615,61 +799,123 @@ tp_status ensure_cg(tp_problem* P, int k)
     TP_TRY(P->cg_p.ensure((size_t)P->nV * k, s));
     TP_TRY(P->cg_red.ensure(cg_red_doubles(k), s));
     TP_TRY(P->cg_bar.ensure(cg_bar_words(k), s));
-    TP_TRY(P->cg_iters.ensure(std::max(k, 64), s));
-    TP_TRY(P->cg_relres.ensure(std::max(k, 64), s));
+    TP_TRY(P->cg_iters.ensure(kMaxCols, s));
+    TP_TRY(P->cg_relres.ensure(kMaxCols, s));
     TP_TRY(P->red.ensure(std::max(reduce_scratch_doubles(16), project_scratch_doubles(k, P->ncomp)), s));
+    if (P->have_pcg) {
+        const size_t n = (size_t)P->nV;
+        const size_t kc = (size_t)std::min(k, kMaxGroupCols);
+        TP_TRY(P->pcg_Vb.ensure(n * kc, s));
+        TP_TRY(P->pcg_rho.ensure((size_t)P->pcg.nb * kc, s));
+        TP_TRY(P->pcg_red.ensure((size_t)2 * P->pcg.nb * 2 * kc, s));
+        TP_TRY(P->pcg_bp.ensure(n * kc, s));
+        TP_TRY(P->pcg_xp.ensure(n * kc, s));
+    }
     return TP_OK;
 }
 
-// x = C^+ b for k columns (row stride k); b is overwritten with its projection.
-tp_status run_cg(tp_problem* P, double* b, double* x, int k, int* it_max, double* res_max)
+// A slot of the batch owner's ring of PCG tables (device + pinned host staging).  A slot
+// is reused only after the copy that last read its staging has run.
+tp_status pcg_table_slot(tp_problem* O, int n, void** dev, void** host, int* slot)
 {
-    TP_TRY(ensure_cotan(P));
-    TP_TRY(ensure_cg(P, k));
-    hipStream_t s = P->stream;
-    TP_HIP(launch_project_mean(b, k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
-    if (P->have_pcg) {
-        // preconditioned solve in block order, up to kMaxGroupCols columns per launch
-        const int64_t n = P->nV;
-        const int kc_max = std::min(k, kMaxGroupCols);
-        TP_TRY(P->pcg_Vb.ensure((size_t)n * kc_max, s));
-        TP_TRY(P->pcg_rho.ensure((size_t)P->pcg.nb * kc_max, s));
-        TP_TRY(P->pcg_red.ensure((size_t)2 * P->pcg.nb * 2 * kc_max, s));
-        TP_TRY(P->pcg_bp.ensure((size_t)n * kc_max, s));
-        TP_TRY(P->pcg_xp.ensure((size_t)n * kc_max, s));
-        PcgWork pw;
-        pw.Vb = P->pcg_Vb.p; pw.rho = P->pcg_rho.p; pw.red = P->pcg_red.p;
-        pw.bar = P->cg_bar.p; pw.flags = P->flags.p;
+    TabRing& T = O->tab;
+    const size_t need = (pcg_table_bytes(n) + 255) / 256 * 256;
+    if (need > T.slot_bytes) {
+        TP_HIP(hipStreamSynchronize(O->stream));
+        TP_TRY(T.dev.ensure(need * kTabSlots, O->stream));
+        TP_TRY(T.host.ensure(need * kTabSlots));
+        T.slot_bytes = need;
+        for (int q = 0; q < kTabSlots; ++q) T.used[q] = false;
+    }
+    for (int q = 0; q < kTabSlots; ++q)
+        if (!T.ev[q]) TP_HIP(hipEventCreateWithFlags(&T.ev[q], hipEventDisableTiming));
+    const int q = T.next;
+    T.next = (q + 1) % kTabSlots;
+    if (T.used[q]) TP_HIP(hipEventSynchronize(T.ev[q]));
+    *dev = T.dev.p + (size_t)q * T.slot_bytes;
+    *host = T.host.p + (size_t)q * T.slot_bytes;
+    *slot = q;
+    return TP_OK;
+}
+
+// x[m] = C^+ b[m] for k columns (row stride k) of every problem; b[m] is overwritten with
+// its per-component mean-zero projection.  Iteration counts and final relative residuals
+// go to the pinned mirrors at offset which * kMaxCols (read them after a sync).
+tp_status enqueue_cg(const Batch& B, double* const* b, double* const* x, int k, int which)
+{
+    if (B.empty()) return TP_OK;
+    hipStream_t s = B[0]->stream;
+    std::vector<size_t> pc, plain;
+    for (size_t m = 0; m < B.size(); ++m) {
+        tp_problem* P = B[m];
+        TP_TRY(ensure_cotan(P));
+        TP_TRY(ensure_cg(P, k));
+        TP_HIP(launch_project_mean(b[m], k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
+        (P->have_pcg ? pc : plain).push_back(m);
+    }
+    if (!pc.empty()) {
+        std::vector<PcgItem> items(pc.size());
         for (int c0 = 0; c0 < k; c0 += kMaxGroupCols) {
             const int kc = std::min(kMaxGroupCols, k - c0);
-            pw.iters = P->cg_iters.p + c0;
-            pw.relres = P->cg_relres.p + c0;
-            TP_HIP(launch_permute_rows(n, kc, P->pcg.perm, k, c0, b, P->pcg_bp.p, true, s));
-            TP_HIP(launch_pcg(P->pcg, P->pcg_bp.p, P->pcg_xp.p, kc, P->prm.cg_rtol, P->prm.cg_maxiter, pw, s));
-            TP_HIP(launch_permute_rows(n, kc, P->pcg.perm, k, c0, P->pcg_xp.p, x, false, s));
+            for (size_t q = 0; q < pc.size(); ++q) {
+                tp_problem* P = B[pc[q]];
+                TP_HIP(launch_permute_rows(P->nV, kc, P->pcg.perm, k, c0, b[pc[q]], P->pcg_bp.p, true, s));
+                PcgItem& it = items[q];
+                it.ps = &P->pcg;
+                it.b = P->pcg_bp.p;
+                it.x = P->pcg_xp.p;
+                it.w.Vb = P->pcg_Vb.p; it.w.rho = P->pcg_rho.p; it.w.red = P->pcg_red.p;
+                it.w.bar = P->cg_bar.p; it.w.flags = P->flags.p;
+                it.w.iters = P->cg_iters.p + c0;
+                it.w.relres = P->cg_relres.p + c0;
+                it.rtol = P->prm.cg_rtol;
+                it.maxiter = P->prm.cg_maxiter;
+            }
+            void *tdev = nullptr, *thost = nullptr;
+            int slot = 0;
+            TP_TRY(pcg_table_slot(B[0], (int)items.size(), &tdev, &thost, &slot));
+            TP_HIP(launch_pcg_batch(items.data(), (int)items.size(), kc, tdev, thost, s));
+            TP_HIP(hipEventRecord(B[0]->tab.ev[slot], s));
+            B[0]->tab.used[slot] = true;
+            for (size_t q = 0; q < pc.size(); ++q) {
+                tp_problem* P = B[pc[q]];
+                TP_HIP(launch_permute_rows(P->nV, kc, P->pcg.perm, k, c0, P->pcg_xp.p, x[pc[q]], false, s));
+            }
         }
-    } else {
+    }
+    for (size_t m : plain) {
+        tp_problem* P = B[m];
         CgWork w;
         w.Z = P->cg_Z.p; w.p = P->cg_p.p; w.red = P->cg_red.p; w.bar = P->cg_bar.p;
         w.iters = P->cg_iters.p; w.relres = P->cg_relres.p; w.flags = P->flags.p;
-        TP_HIP(launch_cg(P->nV, P->ell_col.p, P->ell_val.p, P->ell_w, b, x, k, P->prm.cg_rtol,
+        TP_HIP(launch_cg(P->nV, P->ell_col.p, P->ell_val.p, P->ell_w, b[m], x[m], k, P->prm.cg_rtol,
                          P->prm.cg_maxiter, w, s));
     }
-    TP_HIP(launch_project_mean(x, k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
-    std::vector<int> its(k);
-    std::vector<double> res(k);
-    TP_HIP(hipMemcpyAsync(its.data(), P->cg_iters.p, sizeof(int) * k, hipMemcpyDeviceToHost, s));
-    TP_HIP(hipMemcpyAsync(res.data(), P->cg_relres.p, sizeof(double) * k, hipMemcpyDeviceToHost, s));
-    TP_TRY(check_flags(P));   // synchronises
+    for (size_t m = 0; m < B.size(); ++m) {
+        tp_problem* P = B[m];
+        TP_HIP(launch_project_mean(x[m], k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
+        TP_HIP(hipMemcpyAsync(P->hiters.p + which * kMaxCols, P->cg_iters.p, sizeof(int) * k,
+                              hipMemcpyDeviceToHost, s));
+        TP_HIP(hipMemcpyAsync(P->hrelres.p + which * kMaxCols, P->cg_relres.p, sizeof(double) * k,
+                              hipMemcpyDeviceToHost, s));
+    }
+    return TP_OK;
+}
+
+// Largest iteration count and relative residual of solve `which` (after a sync).
+tp_status cg_result(tp_problem* P, int k, int which, int* it_max, double* res_max)
+{
     int im = 0;
     double rm = 0;
     for (int c = 0; c < k; ++c) {
-        im = std::max(im, its[c]);
-        rm = std::max(rm, res[c]);
+        im = std::max(im, P->hiters.p[which * kMaxCols + c]);
+        const double r = P->hrelres.p[which * kMaxCols + c];
+        rm = (r > rm || std::isnan(r)) ? r : rm;
     }
     *it_max = im;
     *res_max = rm;
-    if (!(rm <= P->prm.cg_rtol)) return fail(TP_E_NOT_CONVERGED, "CG did not reach cg_rtol within cg_maxiter (relres " + std::to_string(rm) + ")");
+    if (!(rm <= P->prm.cg_rtol))
+        return fail(TP_E_NOT_CONVERGED, "CG did not reach cg_rtol within cg_maxiter (relres " + std::to_string(rm) + ")");
     return TP_OK;
 }
 
@@ -695,28 +941,95 @@ struct EventTimer {
     }
 };
 
+// Y[m] = A~^{-1} R[m] = C^+ L^sigma C^+ R[m] columnwise (k columns, row stride k); R is
+// not modified.  Uses W1, W2 of every problem.
+tp_status enqueue_precond(const Batch& B, const double* const* R, int k, double* const* Y,
+                          EventTimer* tm, int mark0)
+{
+    if (B.empty()) return TP_OK;
+    hipStream_t s = B[0]->stream;
+    const size_t nb = B.size();
+    std::vector<double*> w1(nb), w2(nb);
+    std::vector<const double*> w2c(nb);
+    for (size_t m = 0; m < nb; ++m) {
+        tp_problem* P = B[m];
+        const size_t nk = (size_t)P->nV * k;
+        TP_TRY(P->W1.ensure(nk, s));
+        TP_TRY(P->W2.ensure(nk, s));
+        TP_HIP(hipMemcpyAsync(P->W1.p, R[m], nk * sizeof(double), hipMemcpyDeviceToDevice, s));
+        w1[m] = P->W1.p;
+        w2[m] = P->W2.p;
+        w2c[m] = P->W2.p;
+    }
+    TP_TRY(enqueue_cg(B, w1.data(), w2.data(), k, 0));      // W2 = C^+ P R
+    if (tm) tm->mark(mark0);
+    TP_TRY(enqueue_fractional(B, w2c.data(), k, k, w1.data(), k));   // W1 = L W2
+    if (tm) tm->mark(mark0 + 1);
+    TP_TRY(enqueue_cg(B, w1.data(), Y, k, 1));               // Y = C^+ P W1
+    if (tm) tm->mark(mark0 + 2);
+    return TP_OK;
+}
+
+// ------------------------------------------------------------------ single-problem forms
+
+tp_status run_energy(tp_problem* P, double* E)
+{
+    const Batch B{P};
+    TP_TRY(enqueue_energy(B, kSlotE));
+    TP_TRY(enqueue_fetch(B));
+    TP_TRY(sync_batch(B));
+    TP_TRY(flag_status(P));
+    *E = P->hs.p[kSlotE];
+    if (!finite(*E)) return fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
+    return TP_OK;
+}
+
+tp_status run_gradient(tp_problem* P, double* E, double* dE)
+{
+    const Batch B{P};
+    TP_TRY(enqueue_gradient(B, &dE, kSlotE));
+    TP_TRY(enqueue_fetch(B));
+    TP_TRY(sync_batch(B));
+    TP_TRY(flag_status(P));
+    *E = 0.5 * P->hs.p[kSlotE];
+    if (!finite(*E)) return fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
+    return TP_OK;
+}
+
+// Lu[:, c] for columns of u (row stride ldu) into Lu (row stride ldl), k columns.
+tp_status run_fractional(tp_problem* P, const double* u, int ldu, int k, double* Lu, int ldl)
+{
+    const Batch B{P};
+    return enqueue_fractional(B, &u, ldu, k, &Lu, ldl);
+}
+
+// x = C^+ b for k columns (row stride k); b is overwritten with its projection.
+tp_status run_cg(tp_problem* P, double* b, double* x, int k, int* it_max, double* res_max)
+{
+    const Batch B{P};
+    TP_TRY(enqueue_cg(B, &b, &x, k, 0));
+    TP_TRY(enqueue_fetch(B));
+    TP_TRY(sync_batch(B));
+    TP_TRY(flag_status(P));
+    return cg_result(P, k, 0, it_max, res_max);
+}
+
 // x = A~^{-1} b columnwise, k columns, row stride k.  b is not modified.
 tp_status run_precond(tp_problem* P, const double* b, int k, double* x, tp_solve_report* rep)
 {
     TP_TRY(ensure_geometry(P));
     TP_TRY(ensure_lap(P));
-    hipStream_t s = P->stream;
-    const size_t nk = (size_t)P->nV * k;
-    TP_TRY(P->W1.ensure(nk, s));
-    TP_TRY(P->W2.ensure(nk, s));
-    EventTimer tm(s);
+    const Batch B{P};
+    EventTimer tm(P->stream);
     tm.mark(0);
-    TP_HIP(hipMemcpyAsync(P->W1.p, b, nk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    TP_TRY(enqueue_precond(B, &b, k, &x, &tm, 1));
+    TP_TRY(enqueue_fetch(B));
+    TP_TRY(sync_batch(B));
+    TP_TRY(flag_status(P));
     int it1 = 0, it2 = 0;
     double r1 = 0, r2 = 0;
-    tp_status st1 = run_cg(P, P->W1.p, P->W2.p, k, &it1, &r1);          // W2 = C^+ P b
-    if (st1 != TP_OK && st1 != TP_E_NOT_CONVERGED) return st1;
-    tm.mark(1);
-    TP_TRY(run_fractional(P, P->W2.p, k, k, P->W1.p, k));               // W1 = L W2
-    tm.mark(2);
-    tp_status st2 = run_cg(P, P->W1.p, x, k, &it2, &r2);                 // x = C^+ P W1
-    if (st2 != TP_OK && st2 != TP_E_NOT_CONVERGED) return st2;
-    tm.mark(3);
+    const tp_status st1 = cg_result(P, k, 0, &it1, &r1);
+    const tp_status st2 = cg_result(P, k, 1, &it2, &r2);
     if (rep) {
         rep->cg_iters[0] = it1;
         rep->cg_iters[1] = it2;
@@ -726,8 +1039,6 @@ tp_status run_precond(tp_problem* P, const double* b, int k, double* x, tp_solve
         rep->t_ms[1] = tm.ms(1, 2);
         rep->t_ms[2] = tm.ms(2, 3);
         rep->t_ms[3] = tm.ms(0, 3);
-    } else {
-        TP_HIP(hipStreamSynchronize(s));
     }
     if (st1 != TP_OK) return st1;
     return st2;
@@ -806,179 +1117,398 @@ struct HostSolve2 {
     }
 };
 
-tp_status run_step(tp_problem* P, const tp_step_opts* opts_in, tp_step_report* rep, double* dir_out)
-{
+// ------------------------------------------------------------------ descent step
+//
+// One constrained, preconditioned descent step (Sec. 3 and Sec. 5.4 with A~^{-1} in place
+// of the GMRES solve): g = dE; Y = A~^{-1}[g | J_A^T | J_V^T]; Schur system S = J Y; direction
+// x = -(y_g - Y S^{-1} J y_g); Armijo line search on E(f + tau x); corrective projection
+// f <- f + tau x - Y S^{-1} Phi(f + tau x) (Sec. 3.3, Sec. 5.3).
+
+struct StepState {
+    tp_problem* P = nullptr;
     tp_step_opts o;
-    tp_step_opts_default(&o);
-    if (opts_in) o = *opts_in;
-    if (!(o.shrink > 0.0 && o.shrink < 1.0)) return fail(TP_E_INVALID_ARGUMENT, "shrink must lie in (0, 1)");
-    if (o.max_backtracks < 0) return fail(TP_E_INVALID_ARGUMENT, "max_backtracks must be >= 0");
-    hipStream_t s = P->stream;
-    const int64_t n = P->nV;
-    tp_step_report R;
-    std::memset(&R, 0, sizeof(R));
-    EventTimer tm(s);
-    TP_TRY(ensure_initial_measures(P));
-    TP_TRY(ensure_geometry(P));
-    TP_TRY(ensure_cotan(P));
-    const double A0 = std::isnan(o.area_target) ? P->area0 : o.area_target;
-    const double V0 = std::isnan(o.volume_target) ? P->vol0 : o.volume_target;
-    const int kc = (o.constrain_area ? 1 : 0) + (o.constrain_volume ? 1 : 0);
-    const int ncol = 3 * (1 + kc);
-    TP_TRY(P->R.ensure((size_t)n * ncol, s));
-    TP_TRY(P->Y.ensure((size_t)n * ncol, s));
-    TP_TRY(P->gbuf.ensure((size_t)n * 3, s));
-    TP_TRY(P->dir.ensure((size_t)n * 3, s));
-    TP_TRY(P->Vt.ensure((size_t)n * 3, s));
-    TP_TRY(P->scal.ensure(256, s));
-
-    // 1. g = dE
-    tm.mark(0);
-    double E0 = 0;
-    TP_TRY(run_gradient(P, &E0, P->gbuf.p));
-    TP_HIP(launch_copy_cols(n, P->gbuf.p, 3, 3, P->R.p, ncol, s));
-    // 2. constraint rows: area gradient = C f (twice the mean curvature normal), volume gradient
-    int col = 3;
-    if (o.constrain_area) {
-        TP_HIP(launch_spmm(n, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->V.p, 3, 3, P->R.p + col, ncol, s));
-        col += 3;
-    }
-    if (o.constrain_volume) {
-        TP_HIP(launch_volume_gradient(P->V.p, P->F.p, n, P->vf_off.p, P->vf_idx.p, P->R.p, ncol, col, s));
-        col += 3;
-    }
-    tm.mark(1);
-    // 3. Y = A~^{-1} [g | J^T]
-    tp_solve_report sr;
-    tp_status pst = run_precond(P, P->R.p, ncol, P->Y.p, &sr);
-    if (pst != TP_OK && pst != TP_E_NOT_CONVERGED) return pst;
-    R.cg_iters[0] = sr.cg_iters[0];
-    R.cg_iters[1] = sr.cg_iters[1];
-    R.cg_relres[0] = sr.cg_relres[0];
-    R.cg_relres[1] = sr.cg_relres[1];
-    tm.mark(2);
-    // 4. Schur system S = J Y (k x k), rhs = J y_g
-    double Sm[4] = {0, 0, 0, 0}, rhs[2] = {0, 0}, mu[2] = {0, 0};
-    {
-        std::vector<double> h(3);
-        for (int a = 0; a < kc; ++a) {
-            for (int b2 = 0; b2 < kc; ++b2) {
-                TP_HIP(launch_dot_cols(P->R.p + 3 * (1 + a), ncol, P->Y.p + 3 * (1 + b2), ncol, n, 3, P->red.p, P->scal.p, s));
-                TP_TRY(read_scalars(P, P->scal.p, h.data(), 3));
-                Sm[a * kc + b2] = h[0] + h[1] + h[2];
-            }
-            TP_HIP(launch_dot_cols(P->R.p + 3 * (1 + a), ncol, P->Y.p, ncol, n, 3, P->red.p, P->scal.p, s));
-            TP_TRY(read_scalars(P, P->scal.p, h.data(), 3));
-            rhs[a] = h[0] + h[1] + h[2];
-        }
-        if (!HostSolve2::solve(kc, Sm, rhs, mu))
-            return fail(TP_E_SINGULAR_CONSTRAINTS, "Schur complement J A~^{-1} J^T is singular");
-    }
-    // x = -(y_g - Y S^{-1} J y_g)
-    {
-        double cf[2] = {mu[0], mu[1]};
-        int cols[2] = {3, 6};
-        TP_HIP(launch_axpy_block3(n, P->Y.p, ncol, -1.0, P->Y.p, ncol, kc, cf, cols, P->dir.p, 3, s));
-    }
-    double gg[3], gx[3];
-    TP_HIP(launch_dot_cols(P->gbuf.p, 3, P->gbuf.p, 3, n, 3, P->red.p, P->scal.p, s));
-    TP_TRY(read_scalars(P, P->scal.p, gg, 3));
-    TP_HIP(launch_dot_cols(P->gbuf.p, 3, P->dir.p, 3, n, 3, P->red.p, P->scal.p, s));
-    TP_TRY(read_scalars(P, P->scal.p, gx, 3));
-    const double slope = gx[0] + gx[1] + gx[2];
-    R.E = E0;
-    R.grad_norm = std::sqrt(gg[0] + gg[1] + gg[2]);
-    R.slope = slope;
-    R.n_constraints = kc;
-    tm.mark(3);
-
-    // Constraint values at f
-    {
-        double a = 0, v = 0;
-        TP_TRY(total_area_volume(P, P->V.p, &a, &v));
-        int m = 0;
-        if (o.constrain_area) R.phi_before[m++] = a - A0;
-        if (o.constrain_volume) R.phi_before[m++] = v - V0;
-    }
-
-    // 5. Armijo line search on E(f + tau x)
-    double tau = o.tau0;
-    if (!(tau > 0)) {
-        double mx = 0;
-        TP_HIP(launch_max_rownorm3(P->dir.p, n, P->red.p, P->scal.p, s));
-        TP_TRY(read_scalars(P, P->scal.p, &mx, 1));
-        if (!(mx > 0)) return fail(TP_E_NONFINITE, "zero or non-finite descent direction");
-        tau = 0.5 * P->mean_edge / mx;
-    }
+    double A0 = 0, V0 = 0;
+    int kc = 0, ncol = 3;
+    double E0 = 0, Sm[4] = {0, 0, 0, 0}, mu[2] = {0, 0};
+    double tau = 0;
     int bt = 0;
-    double Et = 0;
-    for (;;) {
-        const double cf = tau;
-        const int c0 = 0;
-        TP_HIP(launch_axpy_block3(n, P->V.p, 3, 1.0, P->dir.p, 3, 1, &cf, &c0, P->Vt.p, 3, s));
-        tp_status gs = geometry(P, P->Vt.p);
-        if (gs != TP_OK && gs != TP_E_DEGENERATE_FACE && gs != TP_E_NONFINITE) return gs;
-        bool ok = false;
-        if (gs == TP_OK) {
-            tp_status es = run_energy(P, &Et);
-            if (es != TP_OK && es != TP_E_NONFINITE) return es;
-            ok = (es == TP_OK) && (!o.line_search || Et <= E0 + o.armijo_c * tau * slope);
-        }
-        if (ok || !o.line_search) {
-            if (!ok) return fail(TP_E_NONFINITE, "the fixed step produces a degenerate mesh");
-            break;
-        }
-        if (bt >= o.max_backtracks) {
-            if (gs != TP_OK) return fail(TP_E_NONFINITE, "line search found no valid step");
-            break;
-        }
-        tau *= o.shrink;
-        ++bt;
-    }
-    R.tau = tau;
-    R.backtracks = bt;
-    tm.mark(4);
+    tp_step_report R;
+    tp_status st = TP_OK;
+    double* dir_out = nullptr;
+    bool alive() const { return st == TP_OK || st == TP_E_NOT_CONVERGED; }
+};
 
-    // 6. Corrective projection h = -Y S^{-1} Phi(f + tau x) (geometry now describes Vt)
-    double phi[2] = {0, 0};
-    {
-        double a = 0, v = 0;
-        TP_TRY(total_area_volume(P, P->Vt.p, &a, &v));
-        int m = 0;
-        if (o.constrain_area) phi[m++] = a - A0;
-        if (o.constrain_volume) phi[m++] = v - V0;
-        R.phi_trial[0] = phi[0];
-        R.phi_trial[1] = phi[1];
+// Area and six times the signed volume at Vsrc (the face data must describe Vsrc).
+tp_status enqueue_area_volume(tp_problem* P, const double* Vsrc)
+{
+    hipStream_t s = P->stream;
+    TP_HIP(launch_dot_cols(&P->dx.p[0].w, 4, nullptr, 0, P->nF, 1, P->red.p, P->scal.p + kSlotArea, s));
+    TP_TRY(P->vol6.ensure(P->nF, s));
+    TP_HIP(launch_face_volume(Vsrc, P->F.p, P->nF, P->vol6.p, s));
+    TP_HIP(launch_dot_cols(P->vol6.p, 1, nullptr, 0, P->nF, 1, P->red.p, P->scal.p + kSlotVol6, s));
+    return TP_OK;
+}
+
+void constraint_values(const StepState& S, const double* hs, double* phi)
+{
+    int m = 0;
+    if (S.o.constrain_area) phi[m++] = hs[kSlotArea] - S.A0;
+    if (S.o.constrain_volume) phi[m++] = hs[kSlotVol6] / 6.0 - S.V0;
+}
+
+// The problems of G share a stream, precision, exponents, sigma and column count.
+tp_status step_group(std::vector<StepState*>& G)
+{
+    Batch B;
+    for (StepState* S : G) B.push_back(S->P);
+    hipStream_t s = B[0]->stream;
+    const int ncol = G[0]->ncol;
+    EventTimer tm(s);
+    for (StepState* S : G) {
+        tp_problem* P = S->P;
+        const size_t n = (size_t)P->nV;
+        TP_TRY(P->R.ensure(n * ncol, s));
+        TP_TRY(P->Y.ensure(n * ncol, s));
+        TP_TRY(P->gbuf.ensure(n * 3, s));
+        TP_TRY(P->dir.ensure(n * 3, s));
+        TP_TRY(P->Vt.ensure(n * 3, s));
     }
-    double lam[2] = {0, 0};
-    if (kc > 0 && !HostSolve2::solve(kc, Sm, phi, lam))
-        return fail(TP_E_SINGULAR_CONSTRAINTS, "Schur complement is singular");
+    // 1. g = dE (all problems in one all-pairs launch)
+    tm.mark(0);
     {
-        double cf[2] = {-lam[0], -lam[1]};
-        int cols[2] = {3, 6};
-        TP_HIP(launch_axpy_block3(n, P->Vt.p, 3, 1.0, P->Y.p, ncol, kc, cf, cols, P->V.p, 3, s));
+        std::vector<double*> gp;
+        for (tp_problem* P : B) gp.push_back(P->gbuf.p);
+        TP_TRY(enqueue_gradient(B, gp.data(), kSlotE));
     }
-    if (dir_out) TP_HIP(hipMemcpyAsync(dir_out, P->dir.p, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-    P->cotan_valid = false;
-    P->geom_valid = false;
-    TP_TRY(geometry(P));
+    // 2. right-hand sides: g, area gradient C f (twice the mean curvature normal), volume
+    //    gradient
+    for (StepState* S : G) {
+        tp_problem* P = S->P;
+        const int64_t n = P->nV;
+        TP_HIP(launch_copy_cols(n, P->gbuf.p, 3, 3, P->R.p, ncol, s));
+        int col = 3;
+        if (S->o.constrain_area) {
+            TP_HIP(launch_spmm(n, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->V.p, 3, 3, P->R.p + col, ncol, s));
+            col += 3;
+        }
+        if (S->o.constrain_volume) {
+            TP_HIP(launch_volume_gradient(P->V.p, P->F.p, n, P->vf_off.p, P->vf_idx.p, P->R.p, ncol, col, s));
+            col += 3;
+        }
+    }
+    // 3. Y = A~^{-1} R (shared all-pairs and CG launches)
+    tm.mark(1);
     {
-        double a = 0, v = 0;
-        TP_TRY(total_area_volume(P, P->V.p, &a, &v));
-        int m = 0;
-        if (o.constrain_area) R.phi_after[m++] = a - A0;
-        if (o.constrain_volume) R.phi_after[m++] = v - V0;
+        std::vector<const double*> Rp;
+        std::vector<double*> Yp;
+        for (tp_problem* P : B) {
+            Rp.push_back(P->R.p);
+            Yp.push_back(P->Y.p);
+        }
+        TP_TRY(enqueue_precond(B, Rp.data(), ncol, Yp.data(), &tm, 2));
     }
-    TP_TRY(run_energy(P, &R.E_new));
+    // 4. Schur system S = J Y and J y_g (device dot products of 3 columns each)
+    for (StepState* S : G) {
+        tp_problem* P = S->P;
+        const int64_t n = P->nV;
+        for (int a = 0; a < S->kc; ++a) {
+            for (int b2 = 0; b2 < S->kc; ++b2)
+                TP_HIP(launch_dot_cols(P->R.p + 3 * (1 + a), ncol, P->Y.p + 3 * (1 + b2), ncol, n, 3, P->red.p,
+                                       P->scal.p + kSlotS + 3 * (2 * a + b2), s));
+            TP_HIP(launch_dot_cols(P->R.p + 3 * (1 + a), ncol, P->Y.p, ncol, n, 3, P->red.p,
+                                   P->scal.p + kSlotR + 3 * a, s));
+        }
+    }
+    TP_TRY(enqueue_fetch(B));
+    TP_TRY(sync_batch(B));
+    std::vector<StepState*> L;
+    for (StepState* S : G) {
+        tp_problem* P = S->P;
+        const double* h = P->hs.p;
+        if ((S->st = flag_status(P)) != TP_OK) continue;
+        S->R.cg_iters[0] = 0;
+        const tp_status c1 = cg_result(P, ncol, 0, &S->R.cg_iters[0], &S->R.cg_relres[0]);
+        const tp_status c2 = cg_result(P, ncol, 1, &S->R.cg_iters[1], &S->R.cg_relres[1]);
+        if (c1 != TP_OK) S->st = c1;
+        else if (c2 != TP_OK) S->st = c2;
+        S->E0 = 0.5 * h[kSlotE];
+        if (!finite(S->E0)) {
+            S->st = fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
+            continue;
+        }
+        double rhs[2] = {0, 0};
+        for (int a = 0; a < S->kc; ++a) {
+            for (int b2 = 0; b2 < S->kc; ++b2) {
+                const double* v = h + kSlotS + 3 * (2 * a + b2);
+                S->Sm[a * S->kc + b2] = v[0] + v[1] + v[2];
+            }
+            const double* v = h + kSlotR + 3 * a;
+            rhs[a] = v[0] + v[1] + v[2];
+        }
+        if (!HostSolve2::solve(S->kc, S->Sm, rhs, S->mu)) {
+            S->st = fail(TP_E_SINGULAR_CONSTRAINTS, "Schur complement J A~^{-1} J^T is singular");
+            continue;
+        }
+        L.push_back(S);
+    }
+    // 5. direction x = -(y_g - Y S^{-1} J y_g), slope g.x, default step, constraint values
+    for (StepState* S : L) {
+        tp_problem* P = S->P;
+        const int64_t n = P->nV;
+        const double cf[2] = {S->mu[0], S->mu[1]};
+        const int cols[2] = {3, 6};
+        TP_HIP(launch_axpy_block3(n, P->Y.p, ncol, -1.0, P->Y.p, ncol, S->kc, cf, cols, P->dir.p, 3, s));
+        TP_HIP(launch_dot_cols(P->gbuf.p, 3, P->gbuf.p, 3, n, 3, P->red.p, P->scal.p + kSlotGG, s));
+        TP_HIP(launch_dot_cols(P->gbuf.p, 3, P->dir.p, 3, n, 3, P->red.p, P->scal.p + kSlotGX, s));
+        TP_HIP(launch_max_rownorm3(P->dir.p, n, P->red.p, P->scal.p + kSlotMax, s));
+        TP_TRY(enqueue_area_volume(P, P->V.p));    // face data describes V
+    }
+    {
+        Batch BL;
+        for (StepState* S : L) BL.push_back(S->P);
+        if (!BL.empty()) {
+            TP_TRY(enqueue_fetch(BL));
+            TP_TRY(sync_batch(BL));
+        }
+    }
+    std::vector<StepState*> search;
+    for (StepState* S : L) {
+        const double* h = S->P->hs.p;
+        S->R.E = S->E0;
+        S->R.grad_norm = std::sqrt(h[kSlotGG] + h[kSlotGG + 1] + h[kSlotGG + 2]);
+        S->R.slope = h[kSlotGX] + h[kSlotGX + 1] + h[kSlotGX + 2];
+        S->R.n_constraints = S->kc;
+        constraint_values(*S, h, S->R.phi_before);
+        S->tau = S->o.tau0;
+        if (!(S->tau > 0)) {
+            const double mx = h[kSlotMax];
+            if (!(mx > 0) || !finite(mx)) {
+                S->st = fail(TP_E_NONFINITE, "zero or non-finite descent direction");
+                continue;
+            }
+            S->tau = 0.5 * S->P->mean_edge / mx;
+        }
+        S->bt = 0;
+        search.push_back(S);
+    }
     tm.mark(5);
-    R.t_ms[0] = tm.ms(0, 1);
-    R.t_ms[2] = tm.ms(1, 2);
-    R.t_ms[3] = tm.ms(2, 3);
-    R.t_ms[4] = tm.ms(3, 4);
-    R.t_ms[5] = tm.ms(4, 5);
-    R.t_ms[6] = tm.ms(0, 5);
-    if (rep) *rep = R;
-    return pst;
+
+    // 6. Armijo line search on E(f + tau x): one shared energy launch per round over the
+    //    problems still searching
+    std::vector<StepState*> accepted;
+    while (!search.empty()) {
+        Batch BS;
+        for (StepState* S : search) {
+            tp_problem* P = S->P;
+            const double cf = S->tau;
+            const int c0 = 0;
+            TP_HIP(launch_axpy_block3(P->nV, P->V.p, 3, 1.0, P->dir.p, 3, 1, &cf, &c0, P->Vt.p, 3, s));
+            TP_HIP(launch_face_geom(P->Vt.p, P->nV, P->F.p, P->nF, P->fd, P->flags.p, s));
+            P->geom_valid = false;
+            BS.push_back(P);
+        }
+        TP_TRY(enqueue_energy(BS, kSlotE));
+        TP_TRY(enqueue_fetch(BS));
+        TP_TRY(sync_batch(BS));
+        std::vector<StepState*> next;
+        for (StepState* S : search) {
+            tp_problem* P = S->P;
+            const tp_status gs = flag_status(P);
+            if (gs != TP_OK && gs != TP_E_DEGENERATE_FACE && gs != TP_E_NONFINITE) {
+                S->st = gs;
+                continue;
+            }
+            const double Et = P->hs.p[kSlotE];
+            const bool valid = gs == TP_OK && finite(Et);
+            const bool ok = valid && (!S->o.line_search || Et <= S->E0 + S->o.armijo_c * S->tau * S->R.slope);
+            if (ok || !S->o.line_search) {
+                if (!ok) S->st = fail(TP_E_NONFINITE, "the fixed step produces a degenerate mesh");
+                else accepted.push_back(S);
+                continue;
+            }
+            if (S->bt >= S->o.max_backtracks) {
+                if (!valid) S->st = fail(TP_E_NONFINITE, "line search found no valid step");
+                else accepted.push_back(S);
+                continue;
+            }
+            S->tau *= S->o.shrink;
+            ++S->bt;
+            next.push_back(S);
+        }
+        search.swap(next);
+    }
+    tm.mark(6);
+
+    // 7. corrective projection h = -Y S^{-1} Phi(f + tau x) (face data describes f + tau x)
+    Batch BA;
+    for (StepState* S : accepted) {
+        S->R.tau = S->tau;
+        S->R.backtracks = S->bt;
+        TP_TRY(enqueue_area_volume(S->P, S->P->Vt.p));
+        BA.push_back(S->P);
+    }
+    if (!BA.empty()) {
+        TP_TRY(enqueue_fetch(BA));
+        TP_TRY(sync_batch(BA));
+    }
+    Batch BF;
+    std::vector<StepState*> fin;
+    for (StepState* S : accepted) {
+        tp_problem* P = S->P;
+        double phi[2] = {0, 0}, lam[2] = {0, 0};
+        constraint_values(*S, P->hs.p, phi);
+        S->R.phi_trial[0] = phi[0];
+        S->R.phi_trial[1] = phi[1];
+        if (S->kc > 0 && !HostSolve2::solve(S->kc, S->Sm, phi, lam)) {
+            S->st = fail(TP_E_SINGULAR_CONSTRAINTS, "Schur complement is singular");
+            continue;
+        }
+        const double cf[2] = {-lam[0], -lam[1]};
+        const int cols[2] = {3, 6};
+        TP_HIP(launch_axpy_block3(P->nV, P->Vt.p, 3, 1.0, P->Y.p, ncol, S->kc, cf, cols, P->V.p, 3, s));
+        if (S->dir_out)
+            TP_HIP(hipMemcpyAsync(S->dir_out, P->dir.p, sizeof(double) * 3 * P->nV, hipMemcpyDeviceToDevice, s));
+        P->cotan_valid = false;
+        TP_HIP(launch_face_geom(P->V.p, P->nV, P->F.p, P->nF, P->fd, P->flags.p, s));
+        TP_TRY(enqueue_area_volume(P, P->V.p));
+        BF.push_back(P);
+        fin.push_back(S);
+    }
+    TP_TRY(enqueue_energy(BF, kSlotE));
+    tm.mark(7);
+    if (!BF.empty()) {
+        TP_TRY(enqueue_fetch(BF));
+        TP_TRY(sync_batch(BF));
+    }
+    for (StepState* S : fin) {
+        tp_problem* P = S->P;
+        const tp_status gs = flag_status(P);
+        if (gs != TP_OK) {
+            S->st = gs;
+            continue;
+        }
+        P->geom_valid = true;
+        constraint_values(*S, P->hs.p, S->R.phi_after);
+        S->R.E_new = P->hs.p[kSlotE];
+    }
+    // timings of the group (shared by its problems)
+    const double t[8] = {tm.ms(0, 1), tm.ms(1, 2), tm.ms(1, 4), tm.ms(4, 5),
+                         tm.ms(5, 6), tm.ms(6, 7), tm.ms(0, 7), (double)B.size()};
+    for (StepState* S : G)
+        for (int q = 0; q < 8; ++q) S->R.t_ms[q] = t[q];
+    return TP_OK;
+}
+
+// Steps of n problems with shared launches.  Problems are grouped by (precision,
+// exponents, sigma, number of constraint rows); each group runs as one batch.
+tp_status run_step_batch(tp_problem* const* probs, int n, const tp_step_opts* opts, tp_step_report* reps,
+                         tp_status* sts, double* const* dir_out)
+{
+    if (n < 1 || !probs) return fail(TP_E_INVALID_ARGUMENT, "need at least one problem");
+    std::vector<StepState> S(n);
+    for (int m = 0; m < n; ++m) {
+        if (!probs[m]) return fail(TP_E_INVALID_ARGUMENT, "problem is NULL");
+        for (int q = 0; q < m; ++q)
+            if (probs[q] == probs[m]) return fail(TP_E_INVALID_ARGUMENT, "a problem appears twice in the batch");
+        if (probs[m]->device != probs[0]->device || probs[m]->stream != probs[0]->stream)
+            return fail(TP_E_INVALID_ARGUMENT, "the problems of a batch must share device and stream");
+    }
+    TP_HIP(hipSetDevice(probs[0]->device));
+    for (int m = 0; m < n; ++m) {
+        StepState& T = S[m];
+        T.P = probs[m];
+        std::memset(&T.R, 0, sizeof(T.R));
+        tp_step_opts_default(&T.o);
+        if (opts) T.o = opts[m];
+        T.dir_out = dir_out ? dir_out[m] : nullptr;
+        if (!(T.o.shrink > 0.0 && T.o.shrink < 1.0)) {
+            T.st = fail(TP_E_INVALID_ARGUMENT, "shrink must lie in (0, 1)");
+            continue;
+        }
+        if (T.o.max_backtracks < 0) {
+            T.st = fail(TP_E_INVALID_ARGUMENT, "max_backtracks must be >= 0");
+            continue;
+        }
+        tp_problem* P = T.P;
+        tp_status st = ensure_initial_measures(P);
+        if (st == TP_OK) st = ensure_geometry(P);
+        if (st == TP_OK) st = ensure_cotan(P);
+        if (st != TP_OK) {
+            if (st == TP_E_DEVICE) return st;
+            T.st = st;
+            continue;
+        }
+        T.A0 = std::isnan(T.o.area_target) ? P->area0 : T.o.area_target;
+        T.V0 = std::isnan(T.o.volume_target) ? P->vol0 : T.o.volume_target;
+        T.kc = (T.o.constrain_area ? 1 : 0) + (T.o.constrain_volume ? 1 : 0);
+        T.ncol = 3 * (1 + T.kc);
+    }
+    std::vector<bool> done(n, false);
+    for (int m = 0; m < n; ++m) {
+        if (done[m] || S[m].st != TP_OK) continue;
+        std::vector<StepState*> G;
+        for (int q = m; q < n; ++q) {
+            if (done[q] || S[q].st != TP_OK) continue;
+            const tp_problem* a = S[m].P;
+            const tp_problem* b = S[q].P;
+            if (a->prm.precision == b->prm.precision && a->prm.alpha == b->prm.alpha &&
+                a->prm.beta == b->prm.beta && a->sigma == b->sigma && S[m].ncol == S[q].ncol) {
+                G.push_back(&S[q]);
+                done[q] = true;
+            }
+        }
+        TP_TRY(step_group(G));
+    }
+    tp_status first = TP_OK;
+    for (int m = 0; m < n; ++m) {
+        if (reps) reps[m] = S[m].R;
+        if (sts) sts[m] = S[m].st;
+        if (first == TP_OK && S[m].st != TP_OK) first = S[m].st;
+    }
+    return first;
+}
+
+// Upper bound of the device memory a problem holds after descent steps with kc active
+// constraint rows (the allocations of alloc_faces, ensure_lap, build_pcg, ensure_cg, the
+// pair plans and the step's work arrays, with the ELL width max_degree + 1).
+uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const tp_params& prm, int kc)
+{
+    const double n = (double)nV, f = (double)nF;
+    const int64_t cap = face_capacity(nF, 4);
+    const int ncol = 3 * (1 + kc);
+    const int prec = prm.precision;
+    const double w = (double)max_degree + 1.0;
+    double b = 0;
+    b += 24 * n + 12 * f + (double)cap * (3 * 16 + 2 * 32) + 4 * kNumFlags;
+    // incidence, cotan pattern and values, components, ELL
+    b += 4 * (n + 1) * 3 + 12 * f + 4 * (6 * f + 1) + 12 * n * w + 4 * n + 8 * ncomp + 12 * n * w;
+    // preconditioner
+    if (prm.cg_precond) {
+        const double nb = std::ceil(n / pcg_block_size()) + ncomp;
+        if (nb <= 256) {
+            const double bs = pcg_block_size();
+            b += 4 * n + 13 * n * w + 4 * 2 * (nb + 1) + 4 * nb * pcg_max_neighbors() + 8 * nb + 4 * n +
+                 4 * ncomp + 4 * nb * bs * bs + 8 * nb * nb;
+            b += 3 * 8 * n * kMaxGroupCols + 8 * nb * kMaxGroupCols + 8 * 4 * nb * kMaxGroupCols;
+        }
+    }
+    // CG state and reductions
+    b += 8.0 * (double)cg_state_doubles(nV, ncol) + 8 * n * ncol + 8.0 * (double)cg_red_doubles(ncol) +
+         4.0 * (double)cg_bar_words(ncol) + 12 * kMaxCols;
+    b += 8.0 * (double)std::max(reduce_scratch_doubles(16), project_scratch_doubles(ncol, ncomp)) + 8 * 256;
+    // all-pairs partial sums (shared by the kinds), reduced sums, face averages
+    const PairPlan pe = plan_for(kKindEnergy, prec, 1, nF, cap);
+    const PairPlan pg = plan_for(kKindGrad, prec, 1, nF, cap);
+    const int kf = std::min(ncol, kMaxGroupCols);
+    const PairPlan pf = plan_for(kKindFrac, prec, kf, nF, cap);
+    const double part = std::max({(double)pe.n_split * pe.irows, 7.0 * pg.n_split * pg.irows,
+                                  (double)kf * pf.n_split * pf.irows});
+    const double gface = std::max((double)pe.irows, 7.0 * pg.irows);
+    const double esz = prec == TP_PREC_FP64 ? 8 : 4;
+    b += 8 * part + 8 * gface + 8.0 * kf * pf.irows + (double)cap * ((kf + 3) / 4 * 4) * esz;
+    // step work arrays, per-face volumes and edge lengths, CG tables
+    b += 8 * n * ncol * 4 + 8 * n * 3 * 3 + 16 * f + 4096;
+    return (uint64_t)(b * 1.02) + 65536;
 }
 
 struct ProblemGuard {
@@ -1140,7 +1670,15 @@ tp_status tp_precond_step(tp_problem* P, const tp_step_opts* opts, tp_step_repor
 {
     TP_TRY(bind(P));
     set_error("");
-    return run_step(P, opts, report, direction_out);
+    return run_step_batch(&P, 1, opts, report, nullptr, &direction_out);
+}
+
+tp_status tp_batch_step(tp_problem* const* probs, int n, const tp_step_opts* opts,
+                        tp_step_report* reports, tp_status* statuses)
+{
+    set_error("");
+    if (!probs || n < 1) return fail(TP_E_INVALID_ARGUMENT, "need at least one problem");
+    return run_step_batch(probs, n, opts, reports, statuses, nullptr);
 }
 
 tp_status tp_energy(const double* V, int64_t nV, const int32_t* F, int64_t nF,
@@ -1198,6 +1736,27 @@ tp_status tp_energy_faces(const double* X, const double* N, const double* a, int
     TP_HIP(launch_face_from_quantities(X, N, a, nF, P->fd, P->flags.p, P->stream));
     TP_TRY(check_flags(P));
     return run_energy(P, E_out);
+}
+
+tp_status tp_problem_device_bytes(const tp_problem* P, uint64_t* bytes)
+{
+    if (!P || !bytes) return fail(TP_E_INVALID_ARGUMENT, "NULL argument");
+    *bytes = (uint64_t)P->device_bytes();
+    return TP_OK;
+}
+
+tp_status tp_estimate_device_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp,
+                                   const tp_params* params, int n_constraints, uint64_t* bytes)
+{
+    set_error("");
+    if (!bytes) return fail(TP_E_INVALID_ARGUMENT, "bytes is NULL");
+    if (nV < 3 || nF < 2 || max_degree < 1 || ncomp < 1 || n_constraints < 0 || n_constraints > 2)
+        return fail(TP_E_INVALID_ARGUMENT, "need nV >= 3, nF >= 2, max_degree >= 1, ncomp >= 1, 0 <= n_constraints <= 2");
+    tp_params prm;
+    double sigma = 0;
+    TP_TRY(validate_params(params, prm, sigma));
+    *bytes = estimate_bytes(nV, nF, max_degree, ncomp, prm, n_constraints);
+    return TP_OK;
 }
 
 tp_status tp_profile_enable(int on)

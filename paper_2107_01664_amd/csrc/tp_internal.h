@@ -89,14 +89,32 @@ hipError_t launch_face_from_quantities(const double* X, const double* N, const d
 int64_t face_capacity(int64_t nF, int ni_max);
 PairPlan plan_pairs(int64_t nF, int64_t cap, int ni, int occupancy_per_cu);
 
-// All-pairs kernels.  Partial buffers are [n_split][nacc][irows] doubles.
-hipError_t launch_pairs_energy(const FaceData& fd, const PairPlan& pl, int precision,
-                               double alpha, double beta, double* part, hipStream_t s);
-hipError_t launch_pairs_grad(const FaceData& fd, const PairPlan& pl, int precision,
-                             double alpha, double beta, double* part, hipStream_t s);
+// One problem's share of an all-pairs launch.  A launch covers up to kMaxPairJobs
+// problems of the same precision and exponents; problem m owns the workgroups
+// [block0, block0 + n_itiles * n_split) of a 1-D grid, laid out i-tile fastest.  The
+// arithmetic of a problem does not depend on the other problems of its launch.
+struct PairJob {
+    const float4* fx = nullptr;
+    const float4* fl = nullptr;
+    const float4* fn = nullptr;
+    const double4* dx = nullptr;
+    const double4* dn = nullptr;
+    const void* ub = nullptr;       // face-averaged columns (fractional apply only)
+    double* part = nullptr;         // partial buffer [n_split][nacc][irows]
+    int64_t irows = 0;
+    int n_itiles = 0, tiles_per_split = 0, ntiles_j = 0, block0 = 0;
+};
+constexpr int kMaxPairJobs = 16;
+PairJob make_pair_job(const FaceData& fd, const PairPlan& pl, double* part, const void* ub = nullptr);
+
+// All-pairs kernels over njobs problems (any njobs >= 1; launched in chunks of
+// kMaxPairJobs).  Partial buffers are [n_split][nacc][irows] doubles.
+hipError_t launch_pairs_energy(const PairJob* jobs, int njobs, int precision, double alpha,
+                               double beta, hipStream_t s);
+hipError_t launch_pairs_grad(const PairJob* jobs, int njobs, int precision, double alpha,
+                             double beta, hipStream_t s);
 // ub: face-averaged columns, FP32 [cap][kp] (kp = k rounded up to 4) or FP64 [cap][kp].
-hipError_t launch_pairs_frac(const FaceData& fd, const PairPlan& pl, int precision,
-                             double sigma, const void* ub, int k, int kp, double* part,
+hipError_t launch_pairs_frac(const PairJob* jobs, int njobs, int precision, double sigma, int k,
                              hipStream_t s);
 PairPlan plan_for(int kind, int precision, int k, int64_t nF, int64_t cap);
 
@@ -214,8 +232,22 @@ bool pcg_supported(int64_t nb, int ncomp_blocks_max);
 hipError_t launch_pcg_setup(const PcgSetup& ps, const int32_t* lap_off, const double* lap_val, hipStream_t s);
 hipError_t launch_permute_rows(int64_t n, int k, const int32_t* perm, int ld, int c0, const double* src,
                                double* dst, bool forward, hipStream_t s);
-hipError_t launch_pcg(const PcgSetup& ps, const double* b, double* x, int k, double rtol, int maxiter,
-                      const PcgWork& w, hipStream_t s);
+// One system of a multi-problem solve: b, x in block order, [n][k].
+struct PcgItem {
+    const PcgSetup* ps = nullptr;
+    const double* b = nullptr;
+    double* x = nullptr;
+    PcgWork w;
+    double rtol = 1e-10;
+    int maxiter = 1;
+};
+// Device table entries for n systems (tab_dev) and their pinned host staging (tab_host):
+// the host staging must not be rewritten before the copy enqueued here has run.
+size_t pcg_table_bytes(int n);
+// Solve the n systems (k columns each, k <= kMaxGroupCols) in as few cooperative launches
+// as fit on the device at once; each system's arithmetic is that of a launch of its own.
+hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, void* tab_host,
+                            hipStream_t s);
 
 // ------------------------------------------------------------------ device-side sync
 

@@ -2,10 +2,12 @@
 //
 // Every kernel has the same shape: a workgroup owns an i-tile of kBlock * NI faces S
 // held in registers (NI per thread) and streams a contiguous range of j-tiles of kTileJ
-// faces T through LDS; every lane reads the same T (LDS broadcast).  The grid is
-// (i-tiles) x (j-splits); each workgroup writes its per-face sums for its j-range to a
-// partial buffer, and a separate pass adds the splits in order, so results do not depend
-// on scheduling.  The diagonal S = T is excluded by forcing |d|^2 = 1 where d = 0, which
+// faces T through LDS; every lane reads the same T (LDS broadcast).  Each problem's
+// workgroups form an (i-tiles) x (j-splits) grid; one launch concatenates the grids of up
+// to kMaxPairJobs problems (same-phase work of several meshes in one launch).  Each
+// workgroup writes its per-face sums for its j-range to a partial buffer, and a separate
+// pass adds the splits in order, so results do not depend on scheduling or on the other
+// problems of the launch.  The diagonal S = T is excluded by forcing |d|^2 = 1 where d = 0, which
 // makes every term vanish; only tiles that intersect the i-range take that check.
 //
 // Arithmetic (FP32 variants): pair terms in FP32 on the vector ALUs, per-tile sums in
@@ -18,6 +20,7 @@
 #include <algorithm>
 #include <mutex>
 #include <unordered_map>
+#include <vector>
 
 namespace tp {
 
@@ -94,6 +97,26 @@ struct PowGen {
     }
 };
 
+// ------------------------------------------------------------------ job selection
+
+struct PairBatch {
+    PairJob j[kMaxPairJobs];
+    int n;
+};
+
+// The job of this workgroup: the last one whose first workgroup is at or below blockIdx.x.
+// Every index is a compile-time constant and every condition is uniform, so the selection
+// stays in scalar registers.
+__device__ __forceinline__ PairJob pick_job(const PairBatch& jb)
+{
+    PairJob J = jb.j[0];
+    const int b = blockIdx.x;
+#pragma unroll
+    for (int q = 1; q < kMaxPairJobs; ++q)
+        if (q < jb.n && b >= jb.j[q].block0) J = jb.j[q];
+    return J;
+}
+
 // ------------------------------------------------------------------ tile loading
 
 template <bool HILO>
@@ -150,15 +173,20 @@ __device__ __forceinline__ void energy_tile32(const float4* s_x, const float4* s
 }
 
 template <int NI, bool HILO, class Pow>
-__global__ __launch_bounds__(kBlock) void k_energy32(const float4* __restrict__ fx,
-                                                     const float4* __restrict__ fl,
-                                                     const float4* __restrict__ fn,
-                                                     int tiles_per_split, int ntiles_j, Pow pw,
-                                                     double* __restrict__ part, int64_t irows)
+__global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
 {
+    const PairJob J = pick_job(jb);
+    const int bi = ((int)blockIdx.x - J.block0) % J.n_itiles;
+    const int bs = ((int)blockIdx.x - J.block0) / J.n_itiles;
+    const int tiles_per_split = J.tiles_per_split, ntiles_j = J.ntiles_j;
+    double* __restrict__ part = J.part;
+    const int64_t irows = J.irows;
+    const float4* __restrict__ fx = J.fx;
+    const float4* __restrict__ fl = J.fl;
+    const float4* __restrict__ fn = J.fn;
     __shared__ float4 s_x[kTileJ], s_l[HILO ? kTileJ : 1], s_n[kTileJ];
-    const int64_t ibase = (int64_t)blockIdx.x * (kBlock * NI);
-    const int jt0 = blockIdx.y * tiles_per_split;
+    const int64_t ibase = (int64_t)bi * (kBlock * NI);
+    const int jt0 = bs * tiles_per_split;
     const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
     float3 Sh[NI], Sl[NI], Sn[NI];
     int64_t Si[NI];
@@ -193,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_energy32(const float4* __restrict__ 
         for (int r = 0; r < NI; ++r) acc[r] += (double)c[r];
     }
 #pragma unroll
-    for (int r = 0; r < NI; ++r) part[(int64_t)blockIdx.y * irows + Si[r]] = acc[r];
+    for (int r = 0; r < NI; ++r) part[(int64_t)bs * irows + Si[r]] = acc[r];
 }
 
 // ============================================================== energy + differential (FP32)
@@ -265,18 +293,22 @@ __device__ __forceinline__ void grad_tile32(const float4* s_x, const float4* s_l
 }
 
 template <int NI, bool HILO, class Pow>
-__global__ __launch_bounds__(kBlock) void k_grad32(const float4* __restrict__ fx,
-                                                   const float4* __restrict__ fl,
-                                                   const float4* __restrict__ fn,
-                                                   const double4* __restrict__ dxa,
-                                                   const double4* __restrict__ dn,
-                                                   int tiles_per_split, int ntiles_j, double alpha,
-                                                   double beta, Pow pw, double* __restrict__ part,
-                                                   int64_t irows)
+__global__ __launch_bounds__(kBlock) void k_grad32(PairBatch jb, double alpha, double beta, Pow pw)
 {
+    const PairJob J = pick_job(jb);
+    const int bi = ((int)blockIdx.x - J.block0) % J.n_itiles;
+    const int bs = ((int)blockIdx.x - J.block0) / J.n_itiles;
+    const int tiles_per_split = J.tiles_per_split, ntiles_j = J.ntiles_j;
+    double* __restrict__ part = J.part;
+    const int64_t irows = J.irows;
+    const float4* __restrict__ fx = J.fx;
+    const float4* __restrict__ fl = J.fl;
+    const float4* __restrict__ fn = J.fn;
+    const double4* __restrict__ dxa = J.dx;
+    const double4* __restrict__ dn = J.dn;
     __shared__ float4 s_x[kTileJ], s_l[HILO ? kTileJ : 1], s_n[kTileJ];
-    const int64_t ibase = (int64_t)blockIdx.x * (kBlock * NI);
-    const int jt0 = blockIdx.y * tiles_per_split;
+    const int64_t ibase = (int64_t)bi * (kBlock * NI);
+    const int jt0 = bs * tiles_per_split;
     const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
     float3 Sh[NI], Sl[NI], Sn[NI];
     int64_t Si[NI];
@@ -328,7 +360,7 @@ __global__ __launch_bounds__(kBlock) void k_grad32(const float4* __restrict__ fx
         out[4] = aS * alpha * a[8];
         out[5] = aS * alpha * a[9];
         out[6] = a[10];
-        double* dst = part + (int64_t)blockIdx.y * kGradOut * irows + Si[r];
+        double* dst = part + (int64_t)bs * kGradOut * irows + Si[r];
 #pragma unroll
         for (int m = 0; m < kGradOut; ++m) dst[m * irows] = out[m];
     }
@@ -384,17 +416,22 @@ __device__ __forceinline__ void frac_tile32(const float4* s_x, const float4* s_l
 }
 
 template <int NI, int KC, bool HILO>
-__global__ __launch_bounds__(kBlock) void k_frac32(const float4* __restrict__ fx,
-                                                   const float4* __restrict__ fl,
-                                                   const float* __restrict__ ub,
-                                                   int tiles_per_split, int ntiles_j, float expo,
-                                                   double* __restrict__ part, int64_t irows)
+__global__ __launch_bounds__(kBlock) void k_frac32(PairBatch jb, float expo)
 {
+    const PairJob J = pick_job(jb);
+    const int bi = ((int)blockIdx.x - J.block0) % J.n_itiles;
+    const int bs = ((int)blockIdx.x - J.block0) / J.n_itiles;
+    const int tiles_per_split = J.tiles_per_split, ntiles_j = J.ntiles_j;
+    double* __restrict__ part = J.part;
+    const int64_t irows = J.irows;
+    const float4* __restrict__ fx = J.fx;
+    const float4* __restrict__ fl = J.fl;
+    const float* __restrict__ ub = static_cast<const float*>(J.ub);
     constexpr int KP = KPad<KC>::value;
     __shared__ float4 s_x[kTileJ], s_l[HILO ? kTileJ : 1];
     __shared__ __align__(16) float s_u[kTileJ * KP];
-    const int64_t ibase = (int64_t)blockIdx.x * (kBlock * NI);
-    const int jt0 = blockIdx.y * tiles_per_split;
+    const int64_t ibase = (int64_t)bi * (kBlock * NI);
+    const int jt0 = bs * tiles_per_split;
     const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
     float3 Sh[NI], Sl[NI];
     float Su[NI][KC];
@@ -445,7 +482,7 @@ __global__ __launch_bounds__(kBlock) void k_frac32(const float4* __restrict__ fx
     for (int r = 0; r < NI; ++r)
 #pragma unroll
         for (int cc = 0; cc < KC; ++cc)
-            part[((int64_t)blockIdx.y * KC + cc) * irows + Si[r]] = acc[r][cc];
+            part[((int64_t)bs * KC + cc) * irows + Si[r]] = acc[r][cc];
 }
 
 // ============================================================== FP64 variants
@@ -479,14 +516,19 @@ __device__ __forceinline__ void energy_tile64(const double4* s_x, int64_t j0, do
 }
 
 template <class Pow>
-__global__ __launch_bounds__(kBlock) void k_energy64(const double4* __restrict__ dxa,
-                                                     const double4* __restrict__ dn,
-                                                     int tiles_per_split, int ntiles_j, Pow pw,
-                                                     double* __restrict__ part, int64_t irows)
+__global__ __launch_bounds__(kBlock) void k_energy64(PairBatch jb, Pow pw)
 {
+    const PairJob J = pick_job(jb);
+    const int bi = ((int)blockIdx.x - J.block0) % J.n_itiles;
+    const int bs = ((int)blockIdx.x - J.block0) / J.n_itiles;
+    const int tiles_per_split = J.tiles_per_split, ntiles_j = J.ntiles_j;
+    double* __restrict__ part = J.part;
+    const int64_t irows = J.irows;
+    const double4* __restrict__ dxa = J.dx;
+    const double4* __restrict__ dn = J.dn;
     __shared__ double4 s_x[kTileJ];
-    const int64_t ibase = (int64_t)blockIdx.x * kBlock;
-    const int jt0 = blockIdx.y * tiles_per_split;
+    const int64_t ibase = (int64_t)bi * kBlock;
+    const int jt0 = bs * tiles_per_split;
     const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
     const int64_t Si = ibase + threadIdx.x;
     const double4 x = dxa[Si], n = dn[Si];
@@ -500,7 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_energy64(const double4* __restrict__
         if (tile_hits_diag(j0, ibase, kBlock)) energy_tile64<true>(s_x, j0, S, N, Si, pw, acc);
         else energy_tile64<false>(s_x, j0, S, N, Si, pw, acc);
     }
-    part[(int64_t)blockIdx.y * irows + Si] = acc;
+    part[(int64_t)bs * irows + Si] = acc;
 }
 
 template <bool DIAG, class Pow>
@@ -542,15 +584,19 @@ __device__ __forceinline__ void grad_tile64(const double4* s_x, const double4* s
 }
 
 template <class Pow>
-__global__ __launch_bounds__(kBlock) void k_grad64(const double4* __restrict__ dxa,
-                                                   const double4* __restrict__ dn,
-                                                   int tiles_per_split, int ntiles_j, double alpha,
-                                                   double beta, Pow pw, double* __restrict__ part,
-                                                   int64_t irows)
+__global__ __launch_bounds__(kBlock) void k_grad64(PairBatch jb, double alpha, double beta, Pow pw)
 {
+    const PairJob J = pick_job(jb);
+    const int bi = ((int)blockIdx.x - J.block0) % J.n_itiles;
+    const int bs = ((int)blockIdx.x - J.block0) / J.n_itiles;
+    const int tiles_per_split = J.tiles_per_split, ntiles_j = J.ntiles_j;
+    double* __restrict__ part = J.part;
+    const int64_t irows = J.irows;
+    const double4* __restrict__ dxa = J.dx;
+    const double4* __restrict__ dn = J.dn;
     __shared__ double4 s_x[kTileJ], s_n[kTileJ];
-    const int64_t ibase = (int64_t)blockIdx.x * kBlock;
-    const int jt0 = blockIdx.y * tiles_per_split;
+    const int64_t ibase = (int64_t)bi * kBlock;
+    const int jt0 = bs * tiles_per_split;
     const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
     const int64_t Si = ibase + threadIdx.x;
     const double4 x = dxa[Si], n = dn[Si];
@@ -575,22 +621,27 @@ __global__ __launch_bounds__(kBlock) void k_grad64(const double4* __restrict__ d
     out[4] = aS * alpha * a[8];
     out[5] = aS * alpha * a[9];
     out[6] = a[10];
-    double* dst = part + (int64_t)blockIdx.y * kGradOut * irows + Si;
+    double* dst = part + (int64_t)bs * kGradOut * irows + Si;
 #pragma unroll
     for (int m = 0; m < kGradOut; ++m) dst[m * irows] = out[m];
 }
 
 template <int KC>
-__global__ __launch_bounds__(kBlock) void k_frac64(const double4* __restrict__ dxa,
-                                                   const double* __restrict__ ub,
-                                                   int tiles_per_split, int ntiles_j, double expo,
-                                                   double* __restrict__ part, int64_t irows)
+__global__ __launch_bounds__(kBlock) void k_frac64(PairBatch jb, double expo)
 {
+    const PairJob J = pick_job(jb);
+    const int bi = ((int)blockIdx.x - J.block0) % J.n_itiles;
+    const int bs = ((int)blockIdx.x - J.block0) / J.n_itiles;
+    const int tiles_per_split = J.tiles_per_split, ntiles_j = J.ntiles_j;
+    double* __restrict__ part = J.part;
+    const int64_t irows = J.irows;
+    const double4* __restrict__ dxa = J.dx;
+    const double* __restrict__ ub = static_cast<const double*>(J.ub);
     constexpr int KP = KPad<KC>::value;
     __shared__ double4 s_x[kTileJ];
     __shared__ double s_u[kTileJ * KP];
-    const int64_t ibase = (int64_t)blockIdx.x * kBlock;
-    const int jt0 = blockIdx.y * tiles_per_split;
+    const int64_t ibase = (int64_t)bi * kBlock;
+    const int jt0 = bs * tiles_per_split;
     const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
     const int64_t Si = ibase + threadIdx.x;
     const double4 x = dxa[Si];
@@ -618,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_frac64(const double4* __restrict__ d
         }
     }
 #pragma unroll
-    for (int cc = 0; cc < KC; ++cc) part[((int64_t)blockIdx.y * KC + cc) * irows + Si] = acc[cc];
+    for (int cc = 0; cc < KC; ++cc) part[((int64_t)bs * KC + cc) * irows + Si] = acc[cc];
 }
 
 // ============================================================== split reduction
@@ -776,76 +827,135 @@ PairPlan plan_for(int kind, int precision, int k, int64_t nF, int64_t cap)
     return plan_pairs(nF, cap, ni_of(kind, precision), occupancy_of(fn));
 }
 
-hipError_t launch_pairs_energy(const FaceData& fd, const PairPlan& pl, int precision,
-                               double alpha, double beta, double* part, hipStream_t s)
+PairJob make_pair_job(const FaceData& fd, const PairPlan& pl, double* part, const void* ub)
 {
-    const dim3 grid(pl.n_itiles, pl.n_split), block(kBlock);
-    const bool p6 = is_p6(alpha, beta);
-    const PowGen g = make_gen(alpha, beta);
-    if (precision == TP_PREC_FP64) {
-        if (p6) hipLaunchKernelGGL(k_energy64<PowP6>, grid, block, 0, s, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, PowP6{}, part, pl.irows);
-        else hipLaunchKernelGGL(k_energy64<PowGen>, grid, block, 0, s, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, g, part, pl.irows);
-    } else if (precision == TP_PREC_FP32_HILO) {
-        if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, PowP6>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, pl.tiles_per_split, pl.ntiles_j, PowP6{}, part, pl.irows);
-        else hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, PowGen>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, pl.tiles_per_split, pl.ntiles_j, g, part, pl.irows);
-    } else {
-        if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, PowP6>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, pl.tiles_per_split, pl.ntiles_j, PowP6{}, part, pl.irows);
-        else hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, PowGen>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, pl.tiles_per_split, pl.ntiles_j, g, part, pl.irows);
-    }
-    return hipGetLastError();
+    PairJob J;
+    J.fx = fd.fx; J.fl = fd.fl; J.fn = fd.fn; J.dx = fd.dx; J.dn = fd.dn;
+    J.ub = ub;
+    J.part = part;
+    J.irows = pl.irows;
+    J.n_itiles = pl.n_itiles;
+    J.tiles_per_split = pl.tiles_per_split;
+    J.ntiles_j = pl.ntiles_j;
+    J.block0 = 0;
+    return J;
 }
 
-hipError_t launch_pairs_grad(const FaceData& fd, const PairPlan& pl, int precision,
-                             double alpha, double beta, double* part, hipStream_t s)
+namespace {
+
+int job_blocks(const PairJob& J)
 {
-    const dim3 grid(pl.n_itiles, pl.n_split), block(kBlock);
+    const int ns = (J.ntiles_j + J.tiles_per_split - 1) / J.tiles_per_split;
+    return J.n_itiles * ns;
+}
+
+// Cut the job list into launches of at most kMaxPairJobs jobs, longest workgroups first
+// (the order changes no result), and call launch(batch, grid) for each.
+template <class F>
+hipError_t for_each_batch(const PairJob* jobs, int njobs, F&& launch)
+{
+    if (njobs < 1) return hipSuccess;
+    std::vector<int> order(njobs);
+    for (int m = 0; m < njobs; ++m) order[m] = m;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return jobs[a].tiles_per_split > jobs[b].tiles_per_split;
+    });
+    for (int m0 = 0; m0 < njobs; m0 += kMaxPairJobs) {
+        PairBatch jb;
+        jb.n = std::min(kMaxPairJobs, njobs - m0);
+        int64_t blocks = 0;
+        for (int q = 0; q < kMaxPairJobs; ++q) {
+            if (q < jb.n) {
+                jb.j[q] = jobs[order[m0 + q]];
+                jb.j[q].block0 = (int)blocks;
+                blocks += job_blocks(jb.j[q]);
+            } else {
+                jb.j[q] = jb.j[0];
+                jb.j[q].block0 = INT32_MAX;
+            }
+        }
+        if (blocks <= 0) continue;
+        if (blocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+        launch(jb, dim3((unsigned)blocks));
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+hipError_t launch_pairs_energy(const PairJob* jobs, int njobs, int precision, double alpha,
+                               double beta, hipStream_t s)
+{
+    const dim3 block(kBlock);
     const bool p6 = is_p6(alpha, beta);
     const PowGen g = make_gen(alpha, beta);
-    if (precision == TP_PREC_FP64) {
-        if (p6) hipLaunchKernelGGL(k_grad64<PowP6>, grid, block, 0, s, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, PowP6{}, part, pl.irows);
-        else hipLaunchKernelGGL(k_grad64<PowGen>, grid, block, 0, s, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, g, part, pl.irows);
-    } else if (precision == TP_PREC_FP32_HILO) {
-        if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, true, PowP6>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, PowP6{}, part, pl.irows);
-        else hipLaunchKernelGGL((k_grad32<kNiGrad32, true, PowGen>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, g, part, pl.irows);
-    } else {
-        if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, false, PowP6>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, PowP6{}, part, pl.irows);
-        else hipLaunchKernelGGL((k_grad32<kNiGrad32, false, PowGen>), grid, block, 0, s, fd.fx, fd.fl, fd.fn, fd.dx, fd.dn, pl.tiles_per_split, pl.ntiles_j, alpha, beta, g, part, pl.irows);
-    }
-    return hipGetLastError();
+    return for_each_batch(jobs, njobs, [&](const PairBatch& jb, dim3 grid) {
+        if (precision == TP_PREC_FP64) {
+            if (p6) hipLaunchKernelGGL(k_energy64<PowP6>, grid, block, 0, s, jb, PowP6{});
+            else hipLaunchKernelGGL(k_energy64<PowGen>, grid, block, 0, s, jb, g);
+        } else if (precision == TP_PREC_FP32_HILO) {
+            if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, PowP6>), grid, block, 0, s, jb, PowP6{});
+            else hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, PowGen>), grid, block, 0, s, jb, g);
+        } else {
+            if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, PowP6>), grid, block, 0, s, jb, PowP6{});
+            else hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, PowGen>), grid, block, 0, s, jb, g);
+        }
+    });
+}
+
+hipError_t launch_pairs_grad(const PairJob* jobs, int njobs, int precision, double alpha,
+                             double beta, hipStream_t s)
+{
+    const dim3 block(kBlock);
+    const bool p6 = is_p6(alpha, beta);
+    const PowGen g = make_gen(alpha, beta);
+    return for_each_batch(jobs, njobs, [&](const PairBatch& jb, dim3 grid) {
+        if (precision == TP_PREC_FP64) {
+            if (p6) hipLaunchKernelGGL(k_grad64<PowP6>, grid, block, 0, s, jb, alpha, beta, PowP6{});
+            else hipLaunchKernelGGL(k_grad64<PowGen>, grid, block, 0, s, jb, alpha, beta, g);
+        } else if (precision == TP_PREC_FP32_HILO) {
+            if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, true, PowP6>), grid, block, 0, s, jb, alpha, beta, PowP6{});
+            else hipLaunchKernelGGL((k_grad32<kNiGrad32, true, PowGen>), grid, block, 0, s, jb, alpha, beta, g);
+        } else {
+            if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, false, PowP6>), grid, block, 0, s, jb, alpha, beta, PowP6{});
+            else hipLaunchKernelGGL((k_grad32<kNiGrad32, false, PowGen>), grid, block, 0, s, jb, alpha, beta, g);
+        }
+    });
 }
 
 template <int KC>
-static void launch_frac_k(const FaceData& fd, const PairPlan& pl, int precision, double expo,
-                          const void* ub, double* part, hipStream_t s)
+static hipError_t launch_frac_k(const PairJob* jobs, int njobs, int precision, double expo,
+                                hipStream_t s)
 {
-    const dim3 grid(pl.n_itiles, pl.n_split), block(kBlock);
-    if (precision == TP_PREC_FP64)
-        hipLaunchKernelGGL(k_frac64<KC>, grid, block, 0, s, fd.dx, (const double*)ub, pl.tiles_per_split, pl.ntiles_j, expo, part, pl.irows);
-    else if (precision == TP_PREC_FP32_HILO)
-        hipLaunchKernelGGL((k_frac32<kNiFrac32, KC, true>), grid, block, 0, s, fd.fx, fd.fl, (const float*)ub, pl.tiles_per_split, pl.ntiles_j, (float)expo, part, pl.irows);
-    else
-        hipLaunchKernelGGL((k_frac32<kNiFrac32, KC, false>), grid, block, 0, s, fd.fx, fd.fl, (const float*)ub, pl.tiles_per_split, pl.ntiles_j, (float)expo, part, pl.irows);
+    const dim3 block(kBlock);
+    return for_each_batch(jobs, njobs, [&](const PairBatch& jb, dim3 grid) {
+        if (precision == TP_PREC_FP64)
+            hipLaunchKernelGGL(k_frac64<KC>, grid, block, 0, s, jb, expo);
+        else if (precision == TP_PREC_FP32_HILO)
+            hipLaunchKernelGGL((k_frac32<kNiFrac32, KC, true>), grid, block, 0, s, jb, (float)expo);
+        else
+            hipLaunchKernelGGL((k_frac32<kNiFrac32, KC, false>), grid, block, 0, s, jb, (float)expo);
+    });
 }
 
-hipError_t launch_pairs_frac(const FaceData& fd, const PairPlan& pl, int precision,
-                             double sigma, const void* ub, int k, int kp, double* part,
+hipError_t launch_pairs_frac(const PairJob* jobs, int njobs, int precision, double sigma, int k,
                              hipStream_t s)
 {
-    (void)kp;
     const double expo = -(2.0 * sigma + 2.0) * 0.5;   // |d|^-(2 sigma + 2) = r2^expo
     switch (k) {
-    case 1: launch_frac_k<1>(fd, pl, precision, expo, ub, part, s); break;
-    case 2: launch_frac_k<2>(fd, pl, precision, expo, ub, part, s); break;
-    case 3: launch_frac_k<3>(fd, pl, precision, expo, ub, part, s); break;
-    case 4: launch_frac_k<4>(fd, pl, precision, expo, ub, part, s); break;
-    case 5: launch_frac_k<5>(fd, pl, precision, expo, ub, part, s); break;
-    case 6: launch_frac_k<6>(fd, pl, precision, expo, ub, part, s); break;
-    case 7: launch_frac_k<7>(fd, pl, precision, expo, ub, part, s); break;
-    case 8: launch_frac_k<8>(fd, pl, precision, expo, ub, part, s); break;
-    case 9: launch_frac_k<9>(fd, pl, precision, expo, ub, part, s); break;
+    case 1: return launch_frac_k<1>(jobs, njobs, precision, expo, s);
+    case 2: return launch_frac_k<2>(jobs, njobs, precision, expo, s);
+    case 3: return launch_frac_k<3>(jobs, njobs, precision, expo, s);
+    case 4: return launch_frac_k<4>(jobs, njobs, precision, expo, s);
+    case 5: return launch_frac_k<5>(jobs, njobs, precision, expo, s);
+    case 6: return launch_frac_k<6>(jobs, njobs, precision, expo, s);
+    case 7: return launch_frac_k<7>(jobs, njobs, precision, expo, s);
+    case 8: return launch_frac_k<8>(jobs, njobs, precision, expo, s);
+    case 9: return launch_frac_k<9>(jobs, njobs, precision, expo, s);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace tp

@@ -25,6 +25,8 @@
 
 #include <algorithm>
 #include <type_traits>
+#include <utility>
+#include <vector>
 
 namespace tp {
 
@@ -212,6 +214,7 @@ struct PcgArgs {
     double rtol;
     int maxiter;
     int k;
+    int block0;               // first workgroup of this problem in its launch
 };
 
 constexpr int kCrowMax = 7680;      // doubles of cached coarse-inverse rows (60 KB)
@@ -245,12 +248,19 @@ __device__ __forceinline__ void wg_reduce(const double (&v)[M], double* wave_sh,
     __syncthreads();
 }
 
+// One launch solves the systems of ntab independent problems: problem m owns workgroups
+// [tab[m].block0, tab[m + 1].block0) and synchronises only among them (its own barrier
+// words), so its iterates are those of a launch of its own.
 template <int KG>
-__global__ __launch_bounds__(kBS) void k_pcg(PcgArgs A)
+__global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, int ntab)
 {
     extern __shared__ __align__(16) char smem_raw[];
     PcgShared<KG>& S = *reinterpret_cast<PcgShared<KG>*>(smem_raw);
-    const int B = blockIdx.x;
+    int pm = 0;
+    for (int q = 1; q < ntab; ++q)
+        if ((int)blockIdx.x >= tab[q].block0) pm = q;
+    const PcgArgs A = tab[pm];
+    const int B = (int)blockIdx.x - A.block0;
     const int nb = A.nb, k = A.k;
     const int64_t n = A.n;
     const int32_t s0 = A.bstart[B], cnt = A.bstart[B + 1] - s0;
@@ -624,48 +634,85 @@ hipError_t launch_permute_rows(int64_t n, int k, const int32_t* perm, int ld, in
     return hipGetLastError();
 }
 
-template <int KG>
-static hipError_t launch_pcg_k(PcgArgs a, hipStream_t s)
+namespace {
+
+const void* pcg_fn(int k)
 {
-    const void* fn = (const void*)k_pcg<KG>;
-    const size_t smem = sizeof(PcgShared<KG>);
+    switch (k) {
+    case 1: return (const void*)k_pcg<1>;
+    case 2: return (const void*)k_pcg<2>;
+    case 3: return (const void*)k_pcg<3>;
+    case 4: return (const void*)k_pcg<4>;
+    case 5: return (const void*)k_pcg<5>;
+    case 6: return (const void*)k_pcg<6>;
+    case 7: return (const void*)k_pcg<7>;
+    case 8: return (const void*)k_pcg<8>;
+    case 9: return (const void*)k_pcg<9>;
+    default: return nullptr;
+    }
+}
+
+}  // namespace
+
+bool pcg_supported(int64_t nb, int ncomp_blocks_max) { (void)ncomp_blocks_max; return nb >= 1 && nb <= kMaxNbPcg; }
+int pcg_block_size() { return kBS; }
+int pcg_max_neighbors() { return kMaxNbn; }
+size_t pcg_table_bytes(int n) { return sizeof(PcgArgs) * (size_t)std::max(n, 1); }
+
+hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, void* tab_host,
+                            hipStream_t s)
+{
+    if (n < 1) return hipSuccess;
+    const void* fn = pcg_fn(k);
+    if (!fn) return hipErrorInvalidValue;
+    const size_t smem = pcg_smem_bytes(k);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     int per_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBS, smem);
     if (e != hipSuccess) return e;
-    if ((int64_t)a.nb > (int64_t)per_cu * device_info().num_cu) return hipErrorCooperativeLaunchTooLarge;
-    void* params[] = {&a};
-    return hipLaunchCooperativeKernel(fn, dim3(a.nb), dim3(kBS), params, smem, s);
-}
-
-bool pcg_supported(int64_t nb, int ncomp_blocks_max) { (void)ncomp_blocks_max; return nb >= 1 && nb <= kMaxNbPcg; }
-int pcg_block_size() { return kBS; }
-int pcg_max_neighbors() { return kMaxNbn; }
-
-hipError_t launch_pcg(const PcgSetup& ps, const double* b, double* x, int k, double rtol, int maxiter,
-                      const PcgWork& w, hipStream_t s)
-{
-    if (k < 1 || k > kMaxGroupCols) return hipErrorInvalidValue;
-    hipError_t e = hipMemsetAsync(w.bar, 0, kBarWordsPerGroup * sizeof(unsigned), s);
-    if (e != hipSuccess) return e;
-    PcgArgs a;
-    a.n = ps.n; a.nb = ps.nb; a.ell_w = ps.ell_w; a.pcol = ps.pcol; a.pval = ps.pval; a.pslot = ps.pslot;
-    a.bstart = ps.bstart; a.badj_off = ps.badj_off; a.badj = ps.badj; a.Binv = ps.Binv; a.C0inv = ps.C0inv;
-    a.b = b; a.x = x; a.Vb = w.Vb; a.rho = w.rho; a.red = w.red; a.bar = w.bar;
-    a.iters = w.iters; a.relres = w.relres; a.flags = w.flags; a.rtol = rtol; a.maxiter = maxiter; a.k = k;
-    switch (k) {
-    case 1: return launch_pcg_k<1>(a, s);
-    case 2: return launch_pcg_k<2>(a, s);
-    case 3: return launch_pcg_k<3>(a, s);
-    case 4: return launch_pcg_k<4>(a, s);
-    case 5: return launch_pcg_k<5>(a, s);
-    case 6: return launch_pcg_k<6>(a, s);
-    case 7: return launch_pcg_k<7>(a, s);
-    case 8: return launch_pcg_k<8>(a, s);
-    case 9: return launch_pcg_k<9>(a, s);
-    default: return hipErrorInvalidValue;
+    const int64_t cap = (int64_t)per_cu * device_info().num_cu;
+    PcgArgs* H = static_cast<PcgArgs*>(tab_host);
+    for (int m = 0; m < n; ++m) {
+        const PcgItem& it = items[m];
+        const PcgSetup& ps = *it.ps;
+        PcgArgs& a = H[m];
+        a.n = ps.n; a.nb = ps.nb; a.ell_w = ps.ell_w; a.pcol = ps.pcol; a.pval = ps.pval; a.pslot = ps.pslot;
+        a.bstart = ps.bstart; a.badj_off = ps.badj_off; a.badj = ps.badj; a.Binv = ps.Binv; a.C0inv = ps.C0inv;
+        a.b = it.b; a.x = it.x; a.Vb = it.w.Vb; a.rho = it.w.rho; a.red = it.w.red; a.bar = it.w.bar;
+        a.iters = it.w.iters; a.relres = it.w.relres; a.flags = it.w.flags;
+        a.rtol = it.rtol; a.maxiter = it.maxiter; a.k = k; a.block0 = 0;
+        if ((int64_t)ps.nb > cap) return hipErrorCooperativeLaunchTooLarge;
     }
+    // launches of consecutive problems whose workgroups are resident together
+    std::vector<std::pair<int, int>> groups;
+    for (int i0 = 0; i0 < n;) {
+        int64_t sum = 0;
+        int i1 = i0;
+        while (i1 < n && sum + H[i1].nb <= cap) {
+            H[i1].block0 = (int)sum;
+            sum += H[i1].nb;
+            ++i1;
+        }
+        groups.emplace_back(i0, i1);
+        i0 = i1;
+    }
+    e = hipMemcpyAsync(tab_dev, tab_host, sizeof(PcgArgs) * n, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    for (int m = 0; m < n; ++m) {
+        e = hipMemsetAsync(items[m].w.bar, 0, kBarWordsPerGroup * sizeof(unsigned), s);
+        if (e != hipSuccess) return e;
+    }
+    for (const auto& g : groups) {
+        const PcgArgs* t = static_cast<const PcgArgs*>(tab_dev) + g.first;
+        int nt = g.second - g.first;
+        int blocks = 0;
+        for (int m = g.first; m < g.second; ++m) blocks += H[m].nb;
+        void* params[] = {(void*)&t, (void*)&nt};
+        e = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kBS), params, smem, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 }  // namespace tp

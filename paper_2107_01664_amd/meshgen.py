@@ -225,6 +225,15 @@ def serving_requests(n: int = 512, seed: int = 0, fmin: float = 2000.0,
     return out
 
 
+def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson process of the given rate (requests/s):
+    cumulative sums of exponential gaps, default_rng(seed); rate = inf gives all zeros."""
+    if not math.isfinite(rate):
+        return np.zeros(n)
+    rng = np.random.default_rng(seed)
+    return np.cumsum(rng.exponential(1.0 / rate, size=n))
+
+
 def build_request_mesh(spec: dict) -> Mesh:
     if spec["kind"] == "sphere":
         m = geodesic_sphere(spec["freq"])

@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtpsurf.so")
 
 TP_OK = 0
+TP_E_INVALID_ARGUMENT, TP_E_NOT_CONVERGED, TP_E_DEVICE = 1, 5, 8
 STATUS_NAMES = {
     0: "TP_OK", 1: "TP_E_INVALID_ARGUMENT", 2: "TP_E_DEGENERATE_FACE", 3: "TP_E_BAD_INDEX",
     4: "TP_E_NONFINITE", 5: "TP_E_NOT_CONVERGED", 6: "TP_E_OUT_OF_MEMORY",
@@ -34,7 +35,8 @@ EXPORTED = [
     "tp_problem_get_vertices", "tp_problem_energy", "tp_problem_gradient",
     "tp_problem_fractional_apply", "tp_problem_precond_apply", "tp_step_opts_default",
     "tp_precond_step", "tp_last_error", "tp_profile_enable", "tp_profile_reset", "tp_profile_get",
-    "tp_problem_poisson_solve",
+    "tp_problem_poisson_solve", "tp_batch_step", "tp_problem_device_bytes",
+    "tp_estimate_device_bytes",
 ]
 
 
@@ -113,6 +115,9 @@ def lib() -> ctypes.CDLL:
         "tp_problem_poisson_solve": [vp, vp, i32, vp, P(SolveReport)],
         "tp_step_opts_default": [P(StepOpts)],
         "tp_precond_step": [vp, P(StepOpts), P(StepReport), vp],
+        "tp_batch_step": [P(vp), i32, P(StepOpts), P(StepReport), P(i32)],
+        "tp_problem_device_bytes": [vp, P(ctypes.c_uint64)],
+        "tp_estimate_device_bytes": [i64, i64, i32, i32, P(Params), i32, P(ctypes.c_uint64)],
         "tp_profile_enable": [i32],
         "tp_profile_reset": [],
         "tp_profile_get": [i32, P(KernelStats)],
@@ -316,6 +321,44 @@ class Problem:
         ptr = direction.data_ptr() if direction is not None else None
         _check(lib().tp_precond_step(self._h, ctypes.byref(opts or step_opts()), ctypes.byref(rep), ptr))
         return rep
+
+    def device_bytes(self) -> int:
+        b = ctypes.c_uint64()
+        _check(lib().tp_problem_device_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
+
+def batch_step(problems, opts=None):
+    """tp_batch_step: one descent step of every problem, same-phase work in shared launches.
+
+    opts: None (defaults), one StepOpts for all, or a list of len(problems).
+    Returns (statuses, reports); a failed problem's status is nonzero, the others are valid.
+    """
+    n = len(problems)
+    if n == 0:
+        return [], []
+    hs = (ctypes.c_void_p * n)(*[p._h.value for p in problems])
+    if opts is None or isinstance(opts, StepOpts):
+        one = opts or step_opts()
+        arr = (StepOpts * n)(*([one] * n))
+    else:
+        if len(opts) != n:
+            raise ValueError("opts must have one entry per problem")
+        arr = (StepOpts * n)(*opts)
+    reps = (StepReport * n)()
+    sts = (ctypes.c_int * n)()
+    rc = lib().tp_batch_step(hs, n, arr, reps, sts)
+    if rc == TP_E_DEVICE or (rc != TP_OK and all(int(x) == TP_OK for x in sts)):
+        _check(rc)      # a failure of the whole call, not of one problem
+    return [int(x) for x in sts], [reps[i] for i in range(n)]
+
+
+def estimate_device_bytes(nV: int, nF: int, max_degree: int, ncomp: int = 1,
+                          params: Optional[Params] = None, n_constraints: int = 2) -> int:
+    b = ctypes.c_uint64()
+    _check(lib().tp_estimate_device_bytes(nV, nF, max_degree, ncomp, ctypes.byref(params or default_params()),
+                                          n_constraints, ctypes.byref(b)))
+    return int(b.value)
 
 
 def profile_enable(on: bool = True):

@@ -1,0 +1,159 @@
+"""Batched descent steps and the serving loop on the GPU: every result in a batch (or in
+the served mix) is bit-identical to the same mesh stepped alone, shared multi-problem
+CG launches split when they do not fit on the device at once, and the device memory a
+problem holds stays under the admission estimate."""
+import numpy as np
+import pytest
+
+from paper_2107_01664_amd import meshgen as mg
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2107_01664_amd import tpsurf
+    tpsurf.lib()
+    return tpsurf
+
+
+def dev(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def mix():
+    return [
+        mg.workload("small_sphere"),                                   # 1,280 faces
+        mg.add_noise(mg.torus(60, 30, 1.0, 0.3), 0.003, 5),           # 3,600 faces
+        mg.add_noise(mg.geodesic_sphere(14), 0.01, 6),                # 3,920 faces
+        mg.linked_tori(24, 12, 1.0, 0.25, 1.0),                       # 1,152 faces, 2 parts
+    ]
+
+
+def steps_alone(tp, m, nsteps, opts):
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        reps = [P.step(opts) for _ in range(nsteps)]
+        return P.vertices().cpu().numpy(), reps
+
+
+def same_report(a, b):
+    for f in ("E", "E_new", "grad_norm", "slope", "tau", "backtracks", "cg_iters", "cg_relres",
+              "phi_after"):
+        x, y = getattr(a, f), getattr(b, f)
+        x = list(x) if hasattr(x, "__len__") else [x]
+        y = list(y) if hasattr(y, "__len__") else [y]
+        if x != y:
+            return f
+    return None
+
+
+def test_batch_step_bit_identical_to_alone(tp):
+    meshes = mix()
+    opts = tp.step_opts()
+    print("[serve] batch of", [m.nF for m in meshes], flush=True)
+    alone = [steps_alone(tp, m, 2, opts) for m in meshes]
+    Ps = [tp.Problem(dev(m.V), dev(m.F, torch.int32)) for m in meshes]
+    try:
+        reps = []
+        for _ in range(2):
+            sts, r = tp.batch_step(Ps, opts)
+            assert sts == [0] * len(Ps), sts
+            reps.append(r)
+        for q, P in enumerate(Ps):
+            V = P.vertices().cpu().numpy()
+            assert np.array_equal(V, alone[q][0]), q
+            for s in range(2):
+                bad = same_report(reps[s][q], alone[q][1][s])
+                assert bad is None, (q, s, bad)
+            assert reps[0][q].t_ms[7] == len(Ps)
+    finally:
+        for P in Ps:
+            P.close()
+
+
+def test_batch_step_groups_of_options(tp):
+    # different constraint sets form different launch groups; each matches its lone step
+    meshes = mix()[:3]
+    optl = [tp.step_opts(), tp.step_opts(constrain_area=0),
+            tp.step_opts(constrain_area=0, constrain_volume=0, tau0=1e-3, line_search=0)]
+    alone = [steps_alone(tp, m, 1, o) for m, o in zip(meshes, optl)]
+    Ps = [tp.Problem(dev(m.V), dev(m.F, torch.int32)) for m in meshes]
+    try:
+        sts, reps = tp.batch_step(Ps, optl)
+        assert sts == [0, 0, 0]
+        for q, P in enumerate(Ps):
+            assert np.array_equal(P.vertices().cpu().numpy(), alone[q][0]), q
+            assert same_report(reps[q], alone[q][1][0]) is None
+            assert reps[q].n_constraints == [2, 1, 0][q]
+    finally:
+        for P in Ps:
+            P.close()
+
+
+def test_batch_cg_split_across_launches(tp):
+    # five tori of 7,200 vertices use 57 preconditioner blocks each; 285 blocks exceed one
+    # co-resident cooperative launch, so the shared solve runs as two launches
+    meshes = [mg.add_noise(mg.torus(120, 60, 1.0, 0.3), 0.002, 10 + q) for q in range(5)]
+    opts = tp.step_opts()
+    alone = [steps_alone(tp, m, 1, opts) for m in meshes]
+    Ps = [tp.Problem(dev(m.V), dev(m.F, torch.int32)) for m in meshes]
+    try:
+        sts, reps = tp.batch_step(Ps, opts)
+        assert sts == [0] * 5
+        for q, P in enumerate(Ps):
+            assert np.array_equal(P.vertices().cpu().numpy(), alone[q][0]), q
+            assert same_report(reps[q], alone[q][1][0]) is None
+    finally:
+        for P in Ps:
+            P.close()
+
+
+def test_batch_step_rejects_bad_batches(tp):
+    m = mix()[0]
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        with pytest.raises(tp.TpError):
+            tp.batch_step([P, P])
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            Q = tp.Problem(dev(m.V), dev(m.F, torch.int32))
+        try:
+            with pytest.raises(tp.TpError):
+                tp.batch_step([P, Q])
+        finally:
+            torch.cuda.synchronize()
+            Q.close()
+
+
+def test_device_bytes_within_estimate(tp):
+    for m in mix() + [mg.add_noise(mg.torus(120, 60, 1.0, 0.3), 0.002, 3)]:
+        deg = int(np.bincount(m.F.reshape(-1), minlength=m.nV).max())
+        ncomp = 2 if m.nF == 1152 else 1
+        est = tp.estimate_device_bytes(m.nV, m.nF, deg, ncomp)
+        with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+            for _ in range(2):
+                P.step()
+            used = P.device_bytes()
+        print(f"[serve] nF={m.nF} device bytes {used} estimate {est}", flush=True)
+        assert 0 < used <= est
+        assert est <= 3 * used + (4 << 20)
+
+
+def test_served_mix_equals_serial(tp):
+    from paper_2107_01664_amd import serve
+    meshes = mix()
+    arr = [0.0, 0.0, 0.02, 0.05]
+    reqs = [serve.Request(q, arr[q], m.V, m.F.astype(np.int32), steps=3) for q, m in enumerate(meshes)]
+    ex = serve.GpuExecutor()
+    res = serve.run(reqs, ex, budget_bytes=8 << 30, max_active=3, keep_vertices=True)
+    ser = serve.run_serial(reqs, ex, keep_vertices=True)
+    assert all(r.status == 0 and len(r.step_done) == 3 for r in res)
+    assert max(max(r.batch_sizes) for r in res) >= 2
+    for a, b in zip(res, ser):
+        assert np.array_equal(a.vertices, b.vertices), a.rid
+        assert a.energies == b.energies
+    s = serve.summary(res)
+    print("[serve] mix", s, flush=True)
+    assert s["steps"] == 12
