@@ -515,7 +515,7 @@ tp_status build_pcg(tp_problem* P, const std::vector<int32_t>& label, int ncomp,
     TP_TRY(up(P->pcg_ncb, ncb));
     TP_TRY(P->pcg_pval.ensure((size_t)w * n, s));
     TP_TRY(P->pcg_Binv.ensure((size_t)nb * BS * BS, s));
-    TP_TRY(P->pcg_C0inv.ensure((size_t)nb * nb, s));
+    TP_TRY(P->pcg_C0inv.ensure((size_t)nb * nb + nb, s));   // + per-block diagonal sums
     TP_HIP(hipStreamSynchronize(s));
     PcgSetup& ps = P->pcg;
     ps.n = n; ps.nb = nb; ps.ell_w = w;
@@ -805,9 +805,9 @@ tp_status ensure_cg(tp_problem* P, int k)
     if (P->have_pcg) {
         const size_t n = (size_t)P->nV;
         const size_t kc = (size_t)std::min(k, kMaxGroupCols);
-        TP_TRY(P->pcg_Vb.ensure(n * kc, s));
-        TP_TRY(P->pcg_rho.ensure((size_t)P->pcg.nb * kc, s));
-        TP_TRY(P->pcg_red.ensure((size_t)2 * P->pcg.nb * 2 * kc, s));
+        TP_TRY(P->pcg_Vb.ensure(2 * n * kc, s));
+        TP_TRY(P->pcg_rho.ensure((size_t)2 * P->pcg.nb * kc, s));
+        TP_TRY(P->pcg_red.ensure((size_t)2 * P->pcg.nb * 3 * kc, s));
         TP_TRY(P->pcg_bp.ensure(n * kc, s));
         TP_TRY(P->pcg_xp.ensure(n * kc, s));
     }
@@ -1489,7 +1489,7 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
             const double bs = pcg_block_size();
             b += 4 * n + 13 * n * w + 4 * 2 * (nb + 1) + 4 * nb * pcg_max_neighbors() + 8 * nb + 4 * n +
                  4 * ncomp + 4 * nb * bs * bs + 8 * nb * nb;
-            b += 3 * 8 * n * kMaxGroupCols + 8 * nb * kMaxGroupCols + 8 * 4 * nb * kMaxGroupCols;
+            b += 4 * 8 * n * kMaxGroupCols + 8 * 2 * nb * kMaxGroupCols + 8 * 6 * nb * kMaxGroupCols;
         }
     }
     // CG state and reductions

@@ -215,12 +215,12 @@ struct PcgSetup {
     const int32_t* bcomp = nullptr;       // [nb] component of each block
     const int32_t* ncomp_blocks = nullptr;// [ncomp] blocks per component
     float* Binv = nullptr;                // [nb][bs][bs], FP32
-    double* C0inv = nullptr;              // [nb][nb]
+    double* C0inv = nullptr;              // [nb][nb], then nb doubles of set-up scratch
 };
 struct PcgWork {
-    double* Vb = nullptr;       // n * k
-    double* rho = nullptr;      // nb * k
-    double* red = nullptr;      // 2 * nb * 2k
+    double* Vb = nullptr;       // 2 * n * k   (two copies, see the kernel)
+    double* rho = nullptr;      // 2 * nb * k
+    double* red = nullptr;      // 2 * nb * 3k
     unsigned* bar = nullptr;
     int* iters = nullptr;
     double* relres = nullptr;

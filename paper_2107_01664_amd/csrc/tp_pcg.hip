@@ -11,16 +11,21 @@
 // term (d / m) 1 1^T per component (d a diagonal scale, m its size), which leaves the action
 // on per-component mean-zero vectors equal to the pseudo-inverse.
 //
-// The solver is the Chronopoulos-Gear form of preconditioned CG: u = M^{-1} r, w = C u,
-// gamma = (r, u), delta = (w, u).  One workgroup of kBS threads owns one block (one row per
-// thread) and keeps its C_BB^{-1} in LDS for the whole solve.  Each iteration has two
-// grid exchanges (two-level counter barriers, bounded spins):
-//   A. after x, r, p, s updates: the block solve v = C_BB^{-1} r_B, the block sums of r
-//      (coarse right-hand side) and sum r^2 are published;
-//   B. after w = C u with u = v + c(block), where the coarse values c of the own and the
-//      neighbouring blocks are formed from the published block sums: (r,u), (w,u).
-// All partial sums are added in block order by every workgroup, so every workgroup takes
-// the same decisions and the result does not depend on scheduling.
+// The solver is the pipelined form of preconditioned CG (Ghysels and Vanroose 2014): with
+// u = M^{-1} r and w = C u, the sums gamma = (r,u), delta = (w,u) and (r,r) of iteration i
+// are reduced in the same grid exchange that applies the preconditioner and the matrix to
+// w_i (m = M^{-1} w_i, n = C m), and the auxiliary recurrences z = n + beta z, q = m + beta q,
+// s = w + beta s, p = u + beta p, x += alpha p, r -= alpha s, u -= alpha q, w -= alpha z
+// carry the rest.  One workgroup of kBS threads owns one block (one row per thread) and
+// keeps its C_BB^{-1} in LDS for the whole solve.  Each iteration has ONE grid exchange
+// (two-level counter barrier, bounded spin): before it, every block publishes its block
+// solve v = C_BB^{-1} w_B, the block sums of w (coarse right-hand side) and its partial
+// sums; after it, every block forms the coarse values of its own and neighbouring blocks,
+// m = v + c(block) and C m from the neighbours' v.  All partial sums are added in block
+// order by every workgroup, so every workgroup takes the same decisions and the result does
+// not depend on scheduling.  The recursive residual drifts from b - C x in the pipelined
+// recurrences; every solve therefore ends by checking the true residual and restarts from
+// it when it has not reached the tolerance.
 #include "tp_internal.h"
 
 #include <algorithm>
@@ -115,43 +120,74 @@ __global__ __launch_bounds__(256) void k_block_inverse(int64_t n, int w, const i
     }
 }
 
-// Coarse matrix rows: C0[B][B'] = sum over rows of B of the entries in columns of B'.
-// One workgroup per block; thread 0 adds in row order (deterministic).
+// Coarse matrix rows: C0[B][B'] = sum over rows of B of the entries in columns of B', and
+// bdiag[B] = sum of the diagonal entries of C over the rows of B.  One workgroup per block;
+// thread 0 adds in row order (deterministic).
 __global__ __launch_bounds__(64) void k_coarse_rows(int64_t n, int w, int nb, const int32_t* __restrict__ pcol,
                                                     const double* __restrict__ pval,
                                                     const int32_t* __restrict__ bstart,
                                                     const int32_t* __restrict__ blk,
-                                                    double* __restrict__ C0)
+                                                    double* __restrict__ C0, double* __restrict__ bdiag)
 {
     extern __shared__ __align__(16) double acc[];   // nb
     const int B = blockIdx.x;
     for (int t = threadIdx.x; t < nb; t += blockDim.x) acc[t] = 0.0;
     __syncthreads();
     if (threadIdx.x == 0) {
+        double dg = 0.0;
         for (int64_t i = bstart[B]; i < bstart[B + 1]; ++i)
-            for (int e = 0; e < w; ++e) acc[blk[pcol[(int64_t)e * n + i]]] += pval[(int64_t)e * n + i];
+            for (int e = 0; e < w; ++e) {
+                const int32_t j = pcol[(int64_t)e * n + i];
+                const double a = pval[(int64_t)e * n + i];
+                acc[blk[j]] += a;
+                if (j == i) dg += a;      // padding entries point at i with value 0
+            }
+        bdiag[B] = dg;
     }
     __syncthreads();
     for (int t = threadIdx.x; t < nb; t += blockDim.x) C0[(int64_t)B * nb + t] = acc[t];
 }
 
-// In-place Gauss-Jordan inverse of the nb x nb coarse matrix (one workgroup, global
-// memory), after adding the per-component rank-one terms.
-__global__ __launch_bounds__(1024) void k_coarse_inverse(int nb, const int32_t* __restrict__ bcomp,
-                                                         const int32_t* __restrict__ ncomp_blocks,
-                                                         double* __restrict__ A)
+// Inverse of the nb x nb coarse matrix after adding the per-component rank-one terms, by
+// Gauss-Jordan elimination in one workgroup: in LDS when the matrix fits (nb <= kCoarseLdsMax),
+// else in global memory.  The rank-one scale of a component of several blocks is the mean
+// diagonal of the coarse matrix over such blocks; a component of one block has a zero
+// coarse entry (C is singular on its constants), so it gets the block's own diagonal sum of
+// C instead (any positive scale gives the same action on mean-zero vectors; this one keeps
+// rounding errors of the block sums from being amplified).
+constexpr int kCoarseThreads = 1024;
+constexpr int kCoarseLdsMax = 140;          // 140 x 140 doubles = 153 KB of LDS
+
+template <bool LDS>
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(int nb, const int32_t* __restrict__ bcomp,
+                                                                   const int32_t* __restrict__ ncomp_blocks,
+                                                                   const double* __restrict__ bdiag,
+                                                                   double* __restrict__ G)
 {
+    extern __shared__ __align__(16) double Ash[];
     __shared__ double fcol[kMaxNbPcg];
     __shared__ double dmean;
+    double* A = LDS ? Ash : G;
+    const int nn = nb * nb;
     if (threadIdx.x == 0) {
         double s = 0.0;
-        for (int i = 0; i < nb; ++i) s += A[(int64_t)i * nb + i];
-        dmean = s / nb;
+        int cnt = 0;
+        for (int i = 0; i < nb; ++i)
+            if (ncomp_blocks[bcomp[i]] > 1) {
+                s += G[(int64_t)i * nb + i];
+                ++cnt;
+            }
+        dmean = cnt > 0 ? s / cnt : 0.0;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
         const int i = t / nb, j = t - i * nb;
-        if (bcomp[i] == bcomp[j]) A[t] += dmean / ncomp_blocks[bcomp[i]];
+        double v = G[t];
+        if (bcomp[i] == bcomp[j]) {
+            const int nc = ncomp_blocks[bcomp[i]];
+            v += nc > 1 ? dmean / nc : bdiag[i];
+        }
+        A[t] = v;
     }
     __syncthreads();
     for (int k = 0; k < nb; ++k) {
@@ -163,7 +199,7 @@ __global__ __launch_bounds__(1024) void k_coarse_inverse(int nb, const int32_t* 
             A[(int64_t)k * nb + j] = (j == k ? 1.0 : A[(int64_t)k * nb + j]) * p;
         __threadfence_block();
         __syncthreads();
-        for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) {
+        for (int t = threadIdx.x; t < nn; t += blockDim.x) {
             const int i = t / nb, j = t - i * nb;
             if (i != k) {
                 const double base = (j == k) ? 0.0 : A[t];
@@ -173,6 +209,8 @@ __global__ __launch_bounds__(1024) void k_coarse_inverse(int nb, const int32_t* 
         __threadfence_block();
         __syncthreads();
     }
+    if (LDS)
+        for (int t = threadIdx.x; t < nn; t += blockDim.x) G[t] = A[t];
 }
 
 // forward: dst[i][c] = src[perm[i]][c0 + c] (dst in block order, row stride k);
@@ -204,9 +242,9 @@ struct PcgArgs {
     const double* C0inv;      // [nb][nb]
     const double* b;          // [n][k] (block order)
     double* x;                // [n][k]
-    double* Vb;               // [n][k] local solves
-    double* rho;              // [nb][k] block sums of r
-    double* red;              // [2][nb][2k] block partial sums, buffer = barrier count % 2
+    double* Vb;               // [2][n][k] block solves, copy = barrier count % 2
+    double* rho;              // [2][nb][k] block sums of the preconditioned vector
+    double* red;              // [2][nb][3k] block partial sums
     unsigned* bar;
     int* iters;
     double* relres;
@@ -297,26 +335,36 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
         cs[e] = in ? A.pslot[(int64_t)e * n + i] : 0;
     }
 
-    // Sums over all blocks (block order is fixed by the reduction tree): thread t adds
-    // blocks t and t + kBS of the published [nb][M/KG][k] array.
-    // Partial sums for the m-th barrier go to buffer m % 2: a buffer is rewritten only after
-    // the next barrier, by which time every reader of it has arrived there.
-    int bcount = 0;
-    auto redbuf = [&]() { return A.red + (int64_t)(bcount & 1) * nb * 2 * k; };
-    auto grid_sum = [&](auto mtag) {
-        // M sums over nb blocks: each value is cut into P parts of consecutive blocks, one
-        // per thread (all loads in flight at once), then the parts are added in order.
+    // Exchange buffers come in two copies: data published before the b-th barrier goes to
+    // copy b % 2 and is read between barriers b and b + 1; the copy is written again only
+    // before barrier b + 2, when every reader has arrived at barrier b + 1.
+    int nbar = 0;
+    auto pub = [&]() { return nbar & 1; };
+    auto got = [&]() { return (nbar - 1) & 1; };
+    auto sync = [&]() -> bool {
+        const bool ok = group_barrier(A.bar, B, nb, A.flags);
+        ++nbar;
+        return ok;
+    };
+    auto vbuf = [&](int c) { return A.Vb + (int64_t)c * n * k; };
+    auto rhob = [&](int c) { return A.rho + (int64_t)c * nb * k; };
+    auto redb = [&](int c) { return A.red + (int64_t)c * nb * 3 * k; };
+
+    // M sums over the nb blocks of the copy c of the published partials ([nb][3][k], the
+    // first M / KG groups): each value is cut into P parts of consecutive blocks, one per
+    // thread (all loads in flight at once), then the parts are added in order.
+    auto grid_sum = [&](auto mtag, int c) {
         constexpr int M = decltype(mtag)::value;
-        const double* red = redbuf();
+        const double* red = redb(c);
         constexpr int P = kBS / M;
         const int chunk = (nb + P - 1) / P;
         const int q = t / P, part = t - q * P;
         if (q < M) {
-            const int g = q / KG, c = q - g * KG;
+            const int g = q / KG, cc = q - g * KG;
             double acc = 0.0;
-            if (c < k) {
+            if (cc < k) {
                 const int b0 = part * chunk, b1 = min(nb, b0 + chunk);
-                for (int bb = b0; bb < b1; ++bb) acc += red[(int64_t)bb * 2 * k + g * k + c];
+                for (int bb = b0; bb < b1; ++bb) acc += red[(int64_t)bb * 3 * k + g * k + cc];
             }
             S.part[q * P + part] = acc;
         }
@@ -327,19 +375,25 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
             S.sums[t] = acc;
         }
         __syncthreads();
-        ++bcount;
     };
 
-    double r[KG], x[KG], p[KG], s[KG], u[KG], w[KG], v[KG];
+    double x[KG], r[KG], u[KG], w[KG], p[KG], s[KG], q[KG], z[KG];
+    double m[KG], an[KG];
 
-    // A: v = C_BB^{-1} r_B; publish v, block sums of r and r^2
-    auto phase_a = [&]() {
+    // One exchange round for the vector y (own rows): before the barrier, v = C_BB^{-1} y_B,
+    // the block sums of y (coarse right-hand side) and, with dots, the block partials of
+    // (r,u), (w,u), (r,r) are published; after it, m = M^{-1} y and an = C M^{-1} y at the
+    // own rows (u = v + c, with the coarse values c of the own and neighbouring blocks), and
+    // with dots S.sums holds the three sums over all blocks.
+    auto round = [&](const double (&y)[KG], bool dots) -> bool {
+        const int cp = pub();
 #pragma unroll
-        for (int c = 0; c < KG; ++c) S.r[t * KG + c] = (act && c < k) ? r[c] : 0.0;
+        for (int c = 0; c < KG; ++c) S.r[t * KG + c] = (act && c < k) ? y[c] : 0.0;
         __syncthreads();
+        double v[KG];
 #pragma unroll
         for (int c = 0; c < KG; ++c) v[c] = 0.0;
-        // padding rows of the block hold r = 0 and an identity block in C_BB^{-1}, so the
+        // padding rows of the block hold y = 0 and an identity block in C_BB^{-1}, so the
         // product runs over all kBS rows with a fixed trip count
 #pragma unroll 8
         for (int j = 0; j < kBS; ++j) {
@@ -347,30 +401,31 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
 #pragma unroll
             for (int c = 0; c < KG; ++c) v[c] += bij * S.r[j * KG + c];
         }
-        double tmp[2 * KG];
+        double tmp[4 * KG];
 #pragma unroll
         for (int c = 0; c < KG; ++c) {
-            tmp[c] = act ? r[c] : 0.0;
-            tmp[KG + c] = act ? r[c] * r[c] : 0.0;
+            const bool on = act && c < k;
+            tmp[c] = on ? y[c] : 0.0;
+            tmp[KG + c] = (on && dots) ? r[c] * u[c] : 0.0;
+            tmp[2 * KG + c] = (on && dots) ? w[c] * u[c] : 0.0;
+            tmp[3 * KG + c] = (on && dots) ? r[c] * r[c] : 0.0;
         }
-        wg_reduce<2 * KG>(tmp, S.wave, S.sums);
+        wg_reduce<4 * KG>(tmp, S.wave, S.sums);
         if (act)
 #pragma unroll
             for (int c = 0; c < KG; ++c)
-                if (c < k) A.Vb[i * k + c] = v[c];
-        if (t < KG && t < k) {
-            A.rho[(int64_t)B * k + t] = S.sums[t];
-            redbuf()[(int64_t)B * 2 * k + t] = S.sums[t];
-            redbuf()[(int64_t)B * 2 * k + k + t] = S.sums[KG + t];
+                if (c < k) vbuf(cp)[i * k + c] = v[c];
+        if (t < KG && t < k) rhob(cp)[(int64_t)B * k + t] = S.sums[t];
+        if (dots && t < 3 * KG) {
+            const int g = t / KG, c = t - g * KG;
+            if (c < k) redb(cp)[(int64_t)B * 3 * k + g * k + c] = S.sums[KG + t];
         }
-    };
-
-    // B: coarse values of the own and neighbouring blocks, u = v + c, w = C u; publish
-    // block sums of (r,u) and (w,u)
-    auto phase_b = [&]() {
-        for (int q = t; q < nb * KG; q += kBS) {
-            const int bb = q / KG, c = q - bb * KG;
-            S.rho[q] = c < k ? A.rho[(int64_t)bb * k + c] : 0.0;
+        if (!sync()) return false;
+        const double* Vb = vbuf(cp);
+        const double* rho = rhob(cp);
+        for (int qq = t; qq < nb * KG; qq += kBS) {
+            const int bb = qq / KG, c = qq - bb * KG;
+            S.rho[qq] = c < k ? rho[(int64_t)bb * k + c] : 0.0;
         }
         __syncthreads();
         // coarse values c(sl) = sum_bb C0inv[nbl[sl]][bb] rho[bb] for the nbn x KG jobs: each
@@ -400,14 +455,14 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
         double acc[KG];
 #pragma unroll
         for (int c = 0; c < KG; ++c) {
-            u[c] = v[c] + S.c[own_slot * KG + c];
+            m[c] = v[c] + S.c[own_slot * KG + c];
             acc[c] = 0.0;
         }
         if (act) {
 #pragma unroll
             for (int e = 0; e < kCache; ++e) {
                 if (e < A.ell_w) {
-                    const double* vj = A.Vb + (int64_t)cj[e] * k;
+                    const double* vj = Vb + (int64_t)cj[e] * k;
 #pragma unroll
                     for (int c = 0; c < KG; ++c)
                         if (c < k) acc[c] += cv[e] * (vj[c] + S.c[cs[e] * KG + c]);
@@ -419,25 +474,22 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
                 const int sl = A.pslot[(int64_t)e * n + i];
 #pragma unroll
                 for (int c = 0; c < KG; ++c)
-                    if (c < k) acc[c] += a * (A.Vb[(int64_t)j * k + c] + S.c[sl * KG + c]);
+                    if (c < k) acc[c] += a * (Vb[(int64_t)j * k + c] + S.c[sl * KG + c]);
             }
         }
-        double tmp[2 * KG];
 #pragma unroll
-        for (int c = 0; c < KG; ++c) {
-            w[c] = acc[c];
-            tmp[c] = act ? r[c] * u[c] : 0.0;
-            tmp[KG + c] = act ? w[c] * u[c] : 0.0;
-        }
-        wg_reduce<2 * KG>(tmp, S.wave, S.sums);
-        if (t < 2 * KG) {
-            const int c = t % KG;
-            if (c < k) redbuf()[(int64_t)B * 2 * k + (t / KG) * k + c] = S.sums[t];
-        }
+        for (int c = 0; c < KG; ++c) an[c] = acc[c];
+        if (dots) grid_sum(std::integral_constant<int, 3 * KG>{}, cp);
+        return true;
     };
 
-    // true residual r = b - C x (x published to A.x before the call); block sums of r^2
-    auto true_residual = [&]() {
+    // true residual r = b - C x; S.sums[0 .. KG) = |r|^2 per column
+    auto true_residual = [&]() -> bool {
+        if (act)
+#pragma unroll
+            for (int c = 0; c < KG; ++c)
+                if (c < k) A.x[i * k + c] = x[c];
+        if (!sync()) return false;
         double acc[KG];
 #pragma unroll
         for (int c = 0; c < KG; ++c) acc[c] = 0.0;
@@ -463,13 +515,14 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
             tmp[c] = r[c] * r[c];
         }
         wg_reduce<KG>(tmp, S.wave, S.sums);
-        if (t < KG && t < k) redbuf()[(int64_t)B * 2 * k + t] = S.sums[t];
+        const int cp = pub();
+        if (t < KG && t < k) redb(cp)[(int64_t)B * 3 * k + t] = S.sums[t];
+        if (!sync()) return false;
+        grid_sum(std::integral_constant<int, KG>{}, cp);
+        return true;
     };
 
-    using C1 = std::integral_constant<int, KG>;
-    using C2 = std::integral_constant<int, 2 * KG>;
-
-    double bb[KG], rr[KG], gam[KG], alpha[KG], beta[KG];
+    double bb[KG], rr[KG], gam[KG], alpha[KG];
     bool done[KG];
     int its[KG];
 #pragma unroll
@@ -478,95 +531,73 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
         x[c] = 0.0;
         its[c] = 0;
         bb[c] = 0.0;
+        rr[c] = 0.0;
+        gam[c] = 0.0;
+        alpha[c] = 0.0;
         done[c] = false;
     }
     int total_it = 0;
     constexpr int kMaxRestarts = 6;
+    bool have_bb = false;
     for (int cycle = 0; cycle <= kMaxRestarts; ++cycle) {
-        // ---- start of a cycle from the current (true) residual r
-#pragma unroll
-        for (int c = 0; c < KG; ++c) p[c] = s[c] = 0.0;
-        phase_a();
-        if (!group_barrier(A.bar, B, nb, A.flags)) return;
-        grid_sum(C2{});
-        bool all = true;
+        // ---- start of a cycle from the current (true) residual r: u = M^{-1} r, w = C u
+        if (!round(r, false)) return;
 #pragma unroll
         for (int c = 0; c < KG; ++c) {
-            rr[c] = S.sums[KG + c];
-            if (cycle == 0) {
-                bb[c] = rr[c];
-                done[c] = (c >= k) || !(bb[c] > 0.0);
+            u[c] = m[c];
+            w[c] = an[c];
+            p[c] = s[c] = q[c] = z[c] = 0.0;
+        }
+        bool first = true;
+        // ---- iterations (pipelined: the sums of iteration i are reduced in the same
+        //      exchange as M^{-1} w_i and C M^{-1} w_i)
+        for (;;) {
+            if (!round(w, true)) return;
+            bool conv = true;
+            const bool can = total_it < A.maxiter;
+#pragma unroll
+            for (int c = 0; c < KG; ++c) {
+                const double g = S.sums[c], d = S.sums[KG + c];
+                rr[c] = S.sums[2 * KG + c];
+                if (!have_bb) {
+                    bb[c] = rr[c];
+                    done[c] = (c >= k) || !(bb[c] > 0.0);
+                }
+                double al = 0.0, be = 0.0;
+                if (!done[c] && sqrt(rr[c] / bb[c]) > A.rtol) {
+                    conv = false;
+                    if (!can) {
+                    } else if (first) {
+                        al = g / d;
+                    } else {
+                        be = g / gam[c];
+                        al = g / (d - be * g / alpha[c]);
+                    }
+                    gam[c] = g;
+                    alpha[c] = al;
+                }
+                // columns that converged (or are done) keep al = be = 0: x, r, u, w stay
+                z[c] = an[c] + be * z[c];
+                q[c] = m[c] + be * q[c];
+                s[c] = w[c] + be * s[c];
+                p[c] = u[c] + be * p[c];
+                x[c] += al * p[c];
+                r[c] -= al * s[c];
+                u[c] -= al * q[c];
+                w[c] -= al * z[c];
             }
-            if (!done[c] && sqrt(rr[c] / bb[c]) <= A.rtol) done[c] = true;
-            all = all && done[c];
-        }
-        __syncthreads();
-        if (all || total_it >= A.maxiter) break;
-        phase_b();
-        if (!group_barrier(A.bar, B, nb, A.flags)) return;
-        grid_sum(C2{});
-#pragma unroll
-        for (int c = 0; c < KG; ++c) {
-            gam[c] = S.sums[c];
-            alpha[c] = done[c] ? 0.0 : gam[c] / S.sums[KG + c];
-            beta[c] = 0.0;
-        }
-        __syncthreads();
-        // ---- iterations
-        bool conv = false;
-        while (total_it < A.maxiter) {
+            have_bb = true;
+            __syncthreads();
+            if (conv || !can) break;
             ++total_it;
 #pragma unroll
-            for (int c = 0; c < KG; ++c) {
-                p[c] = u[c] + beta[c] * p[c];
-                s[c] = w[c] + beta[c] * s[c];
-                x[c] += alpha[c] * p[c];
-                r[c] -= alpha[c] * s[c];
-            }
-            phase_a();
-            if (!group_barrier(A.bar, B, nb, A.flags)) return;
-            grid_sum(C2{});
-            conv = true;
-#pragma unroll
-            for (int c = 0; c < KG; ++c) {
-                if (!done[c]) {
-                    rr[c] = S.sums[KG + c];
-                    its[c] = total_it;
-                    if (sqrt(rr[c] / bb[c]) <= A.rtol) {
-                        alpha[c] = beta[c] = 0.0;   // column frozen until verified
-                    } else {
-                        conv = false;
-                    }
-                }
-            }
-            __syncthreads();
-            if (conv) break;
-            phase_b();
-            if (!group_barrier(A.bar, B, nb, A.flags)) return;
-            grid_sum(C2{});
-#pragma unroll
-            for (int c = 0; c < KG; ++c) {
-                if (!done[c] && sqrt(rr[c] / bb[c]) > A.rtol) {
-                    const double gn = S.sums[c], dn = S.sums[KG + c];
-                    const double bn = gn / gam[c];
-                    alpha[c] = gn / (dn - bn * gn / alpha[c]);
-                    beta[c] = bn;
-                    gam[c] = gn;
-                }
-            }
-            __syncthreads();
-        }
-        // ---- verify: publish x, recompute the true residual, restart if needed
-        if (act)
-#pragma unroll
             for (int c = 0; c < KG; ++c)
-                if (c < k) A.x[i * k + c] = x[c];
-        if (!group_barrier(A.bar, B, nb, A.flags)) return;
-        ++bcount;
-        true_residual();
-        if (!group_barrier(A.bar, B, nb, A.flags)) return;
-        grid_sum(C1{});
-        all = true;
+                if (!done[c] && sqrt(rr[c] / bb[c]) > A.rtol) its[c] = total_it;
+            first = false;
+        }
+        // ---- verify: recompute the true residual, restart from it if needed
+        if (!true_residual()) return;
+        bool all = true;
 #pragma unroll
         for (int c = 0; c < KG; ++c) {
             if (!done[c]) {
@@ -619,10 +650,21 @@ hipError_t launch_pcg_setup(const PcgSetup& ps, const int32_t* lap_off, const do
     hipLaunchKernelGGL(k_block_inverse, dim3(ps.nb), dim3(256), binv_smem, s, ps.n, ps.ell_w, ps.pcol,
                        ps.pval, ps.bstart, ps.whole, ps.Binv);
     if ((e = hipGetLastError()) != hipSuccess) return e;
+    double* bdiag = ps.C0inv + (int64_t)ps.nb * ps.nb;   // scratch tail of the C0inv buffer
     hipLaunchKernelGGL(k_coarse_rows, dim3(ps.nb), dim3(64), sizeof(double) * ps.nb, s, ps.n, ps.ell_w,
-                       ps.nb, ps.pcol, ps.pval, ps.bstart, ps.blk, ps.C0inv);
+                       ps.nb, ps.pcol, ps.pval, ps.bstart, ps.blk, ps.C0inv, bdiag);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_coarse_inverse, dim3(1), dim3(1024), 0, s, ps.nb, ps.bcomp, ps.ncomp_blocks, ps.C0inv);
+    if (ps.nb <= kCoarseLdsMax) {
+        const size_t sm = sizeof(double) * (size_t)ps.nb * ps.nb;
+        e = hipFuncSetAttribute((const void*)k_coarse_inverse<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(double) * kCoarseLdsMax * kCoarseLdsMax));
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_coarse_inverse<true>, dim3(1), dim3(kCoarseThreads), sm, s, ps.nb, ps.bcomp,
+                           ps.ncomp_blocks, bdiag, ps.C0inv);
+    } else {
+        hipLaunchKernelGGL(k_coarse_inverse<false>, dim3(1), dim3(kCoarseThreads), 0, s, ps.nb, ps.bcomp,
+                           ps.ncomp_blocks, bdiag, ps.C0inv);
+    }
     return hipGetLastError();
 }
 
