@@ -45,6 +45,12 @@ def parse():
     ap.add_argument("--precision", type=int, default=0, help="0 fp32 hi/lo, 1 fp32, 2 fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="requests of the serving comparison (0 skips it)")
+    ap.add_argument("--serve-fmax", type=float, default=20000.0)
+    ap.add_argument("--serve-steps", type=int, default=4)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving comparison and print its JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 256 MiB device copy 5 times (counter calibration)")
     return ap.parse_args()
@@ -109,12 +115,91 @@ def cpu_baseline(mesh, u, target_s: float):
     }
 
 
+def _build(spec):
+    from paper_2107_01664_amd import meshgen as mg
+    m = mg.build_request_mesh(spec)
+    return m.V, m.F
+
+
+def serving_meshes(n_req: int, fmax: float, steps: int, seed: int = 0, workers: int = 1):
+    """Request specs and meshes; with workers > 1 the meshes are built in forked worker
+    processes, which must happen before this process touches the GPU."""
+    from paper_2107_01664_amd import meshgen as mg
+    specs = mg.serving_requests(n_req, seed, 2000.0, fmax, steps)
+    if workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            built = pool.map(_build, specs)
+    else:
+        built = [_build(sp) for sp in specs]
+    return specs, built
+
+
+def serving_bench(specs, built, steps: int, fmax: float, seed: int = 0, load: float = 0.8,
+                  max_active: int = 16, small_faces: int = 32768, max_large: int = 2,
+                  verbose: bool = False):
+    """Continuous batching against the serial one-mesh-at-a-time path on the same requests:
+    noisy icospheres / tori with F log-uniform in [2,000, fmax], `steps` descent steps
+    each.  The serial path first runs with every request present at t = 0, which gives its
+    capacity (and the batched path is run the same way); both paths then serve Poisson
+    arrivals at `load` x that capacity."""
+    import numpy as np
+    from paper_2107_01664_amd import meshgen as mg
+    from paper_2107_01664_amd import serve
+
+    n_req = len(specs)
+
+    def requests(arrivals):
+        return [serve.Request(sp["id"], float(t), V, F.astype(np.int32), steps)
+                for sp, (V, F), t in zip(specs, built, arrivals)]
+
+    def progress(tag):
+        def f(r):
+            print(f"[serve] {tag} request {r.rid} nF={r.nF} steps={len(r.step_done)} "
+                  f"done at {r.finished:.2f} s", file=sys.stderr, flush=True)
+        return f if verbose else None
+
+    ex = serve.GpuExecutor()
+    serve.run_serial(requests(np.zeros(1))[:1], ex)                  # warm-up
+    zero = np.zeros(n_req)
+    sat_ser = serve.run_serial(requests(zero), ex, on_done=progress("saturated serial"))
+    lanes = dict(small_faces=small_faces, max_large=max_large)
+    sat_bat = serve.run(requests(zero), ex, budget_bytes=200 << 30, max_active=max_active,
+                        on_done=progress("saturated batched"), **lanes)
+    cap = n_req / max(serve.summary(sat_ser)["makespan_s"], 1e-9)      # requests/s
+    rate = load * cap
+    arr = mg.poisson_arrivals(n_req, rate, seed + 1)
+    bat = serve.run(requests(arr), ex, budget_bytes=200 << 30, max_active=max_active,
+                    keep_vertices=True, on_done=progress("poisson batched"), **lanes)
+    ser = serve.run_serial(requests(arr), ex, keep_vertices=True, on_done=progress("poisson serial"))
+    same = all(np.array_equal(a.vertices, b.vertices) for a, b in zip(bat, ser))
+    nf = np.array([sp["nF"] for sp in specs], dtype=float)
+    return {
+        "workload": (f"{n_req} requests, noisy icosphere/torus, F log-uniform in [2000, {int(fmax)}] "
+                     f"(mean {nf.mean():.0f}), {steps} preconditioned steps each (FP32 pair terms, FP64 CG, "
+                     f"area + volume constraints, Armijo), Poisson arrivals at {load} x serial capacity "
+                     f"({rate:.2f} requests/s); batched path: meshes of up to {small_faces} faces share "
+                     f"steps ({max_active} at most), larger ones ({max_large} admitted at most) step one at "
+                     f"a time between the shared steps; 'saturated': every request present at t = 0"),
+        "serial_capacity_req_per_s": cap,
+        "saturated": {"batched": serve.summary(sat_bat), "serial": serve.summary(sat_ser)},
+        "batched": serve.summary(bat),
+        "serial": serve.summary(ser),
+        "all_requests_identical_to_serial": bool(same),
+    }
+
+
 def main():
     a = parse()
     if a.gpus != 1:
         print(f"bench.py: the path runs on one GPU; --gpus {a.gpus} is not supported",
               file=sys.stderr)
         sys.exit(2)
+
+    serve_mesh = None
+    if a.serve_only:        # build the request meshes in worker processes before any GPU use
+        serve_mesh = serving_meshes(a.serve_requests, a.serve_fmax, a.serve_steps,
+                                    workers=min(16, os.cpu_count() or 1))
 
     import numpy as np
     import torch
@@ -128,6 +213,9 @@ def main():
         copy_probe()
         return
     tp.lib()
+    if a.serve_only:
+        print(json.dumps(serving_bench(*serve_mesh, a.serve_steps, a.serve_fmax, verbose=True)), flush=True)
+        return
     dev = torch.device("cuda", 0)
     mesh = mg.workload("torus40k")
     u_np = mg.random_columns(mesh.nV, 3, 1)
@@ -175,7 +263,7 @@ def main():
     cg_ms = [float(np.mean([r.t_ms[0] for r in reps])), float(np.mean([r.t_ms[2] for r in reps]))]
 
     out = {
-        "metric": "tri-pair interactions/s (E+dE, H-apply) vs FP32 roofline",
+        "metric": "tri-pair interactions/s (E+dE, H-apply) vs FP32 roofline; served steps/s + p99",
         "value": value,
         "unit": "tri-pair interactions/s",
         "n_gpus": 1,
@@ -225,6 +313,9 @@ def main():
         "energy": E,
     }
     P.close()
+    if a.serve_requests > 0:
+        out["serving"] = serving_bench(*serving_meshes(a.serve_requests, a.serve_fmax, a.serve_steps),
+                                       a.serve_steps, a.serve_fmax)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, u_np, a.cpu_seconds)
     print(json.dumps(out), flush=True)

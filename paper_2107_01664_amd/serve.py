@@ -98,64 +98,100 @@ class GpuExecutor:
 
 def run(requests: Sequence[Request], executor, budget_bytes: int, max_active: int = 16,
         clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
-        keep_vertices: bool = False) -> List[Result]:
-    """Continuous batching: admit by arrival, slot and memory; one shared step per round."""
-    pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
-    results = {r.rid: Result(r.rid, r.arrival, int(r.F.shape[0])) for r in pending}
-    active: list = []          # [request, handle, steps_done]
+        keep_vertices: bool = False, on_done: Optional[Callable[[Result], None]] = None,
+        small_faces: Optional[int] = None, max_large: int = 2) -> List[Result]:
+    """Continuous batching: admit by arrival, slot and memory; shared steps in rounds.
+
+    With small_faces None every admitted mesh takes part in every shared step.  With
+    small_faces set, meshes with more faces form a second lane: rounds alternate between one
+    shared step of all admitted small meshes and one step of the next large mesh (round
+    robin), so a small mesh's step never waits for more than one large step.  Each lane
+    admits in arrival order (small meshes may overtake large ones); memory is shared.
+    """
+    reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
+    results = {r.rid: Result(r.rid, r.arrival, int(r.F.shape[0])) for r in reqs}
+    if small_faces is None:
+        lanes = [{"pending": reqs, "limit": max_active, "one": False}]
+    else:
+        lanes = [{"pending": [r for r in reqs if r.F.shape[0] <= small_faces], "limit": max_active, "one": False},
+                 {"pending": [r for r in reqs if r.F.shape[0] > small_faces], "limit": max_large, "one": True}]
+    for ln in lanes:
+        ln.update(qi=0, active=[], rr=0)
     used = 0
+    turn = 0
     t0 = clock()
-    qi = 0
-    while qi < len(pending) or active:
+
+    def busy():
+        return any(ln["qi"] < len(ln["pending"]) or ln["active"] for ln in lanes)
+
+    while busy():
         now = clock() - t0
-        # admission in arrival order; a request that does not fit waits (no overtaking)
-        while qi < len(pending) and pending[qi].arrival <= now and len(active) < max_active:
-            req = pending[qi]
-            need = int(executor.estimate(req))
-            res = results[req.rid]
-            if need > budget_bytes:
-                res.status = -1            # larger than the whole budget: rejected
-                res.finished = now
-                qi += 1
-                continue
-            if used + need > budget_bytes:
-                break
-            h = executor.create(req)
-            used += need
-            res.reserved_bytes = need
-            res.admitted = clock() - t0
-            active.append([req, h, 0])
-            qi += 1
-        if not active:
-            if qi < len(pending):
-                sleep(max(0.0, pending[qi].arrival - (clock() - t0)))
+        # admission: each lane in arrival order; a request that does not fit waits
+        for ln in lanes:
+            pend, act = ln["pending"], ln["active"]
+            while ln["qi"] < len(pend) and pend[ln["qi"]].arrival <= now and len(act) < ln["limit"]:
+                req = pend[ln["qi"]]
+                need = int(executor.estimate(req))
+                res = results[req.rid]
+                if need > budget_bytes:
+                    res.status = -1            # larger than the whole budget: rejected
+                    res.finished = now
+                    ln["qi"] += 1
+                    continue
+                if used + need > budget_bytes:
+                    break
+                h = executor.create(req)
+                used += need
+                res.reserved_bytes = need
+                res.admitted = clock() - t0
+                act.append([req, h, 0])
+                ln["qi"] += 1
+        ready = [q for q, ln in enumerate(lanes) if ln["active"]]
+        if not ready:
+            nxt = [ln["pending"][ln["qi"]].arrival for ln in lanes if ln["qi"] < len(ln["pending"])]
+            if nxt:
+                sleep(max(0.0, min(nxt) - (clock() - t0)))
             continue
-        sts, energies = executor.step([a[1] for a in active])
+        q = turn % len(lanes)
+        if q not in ready:
+            q = ready[0]
+        turn = q + 1
+        ln = lanes[q]
+        if ln["one"]:
+            k = ln["rr"] % len(ln["active"])
+            ln["rr"] = k + 1
+            batch = [ln["active"][k]]
+        else:
+            batch = list(ln["active"])
+        sts, energies = executor.step([a[1] for a in batch])
         t = clock() - t0
-        keep = []
-        for a, st, e in zip(active, sts, energies):
+        gone = set()
+        for a, st, e in zip(batch, sts, energies):
             req, h, _ = a
             res = results[req.rid]
             a[2] += 1
             res.step_done.append(t)
             res.energies.append(e)
-            res.batch_sizes.append(len(active))
+            res.batch_sizes.append(len(batch))
             if st != 0 and st != 5:        # 5: CG not converged, step still taken
                 res.status = st
-            if a[2] >= req.steps or res.status not in (0,):
+            if a[2] >= req.steps or res.status != 0:
                 res.finished = t
                 if keep_vertices:
                     res.vertices = executor.vertices(h)
                 executor.destroy(h)
                 used -= res.reserved_bytes
-            else:
-                keep.append(a)
-        active = keep
+                gone.add(id(a))
+                if on_done:
+                    on_done(res)
+        if gone:
+            ln["active"] = [a for a in ln["active"] if id(a) not in gone]
     return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
 
 
 def run_serial(requests: Sequence[Request], executor, clock: Callable[[], float] = time.perf_counter,
-               sleep: Callable[[float], None] = time.sleep, keep_vertices: bool = False) -> List[Result]:
+               sleep: Callable[[float], None] = time.sleep, keep_vertices: bool = False,
+               on_done: Optional[Callable[[Result], None]] = None) -> List[Result]:
     """One request at a time in arrival order, each step on that mesh alone."""
     pending = sorted(requests, key=lambda r: (r.arrival, r.rid))
     results = {}
@@ -180,6 +216,8 @@ def run_serial(requests: Sequence[Request], executor, clock: Callable[[], float]
             res.vertices = executor.vertices(h)
         executor.destroy(h)
         results[req.rid] = res
+        if on_done:
+            on_done(res)
     return [results[r.rid] for r in sorted(requests, key=lambda r: r.rid)]
 
 

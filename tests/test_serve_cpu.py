@@ -42,7 +42,7 @@ class FakeExecutor:
 
     def step(self, handles):
         assert len(set(handles)) == len(handles)
-        self.batches.append(list(handles))
+        self.batches.append([self.live[h][0].rid for h in handles])
         cost = self.overhead
         sts, es = [], []
         for h in handles:
@@ -169,3 +169,31 @@ def test_summary_latencies():
     assert s["steps"] == 15
     assert s["step_latency_ms"]["p50"] == pytest.approx(np.percentile(np.array(lat) * 1e3, 50))
     assert all(x > 0 for x in lat)
+
+
+def test_lanes_bound_small_request_latency():
+    # two large meshes (long steps) and a stream of small ones: with lanes, a small mesh's
+    # step waits for at most one large step; with a single lane it waits for all of them
+    rng = np.random.default_rng(3)
+    V = np.zeros((10, 3))
+    big = [serve.Request(q, 0.0, V, np.zeros((200000, 3), np.int32), steps=6) for q in range(2)]
+    small = [serve.Request(2 + q, 0.01 * q, V, np.zeros((int(rng.integers(2000, 8000)), 3), np.int32), steps=3)
+             for q in range(12)]
+    reqs = big + small
+    lat = {}
+    for policy in (None, 50000):
+        clk = SimClock()
+        ex = FakeExecutor(clk, 10**12, overhead=1e-3, per_face=1e-7)
+        res = serve.run(reqs, ex, 10**12, 16, clock=clk, sleep=clk.sleep, small_faces=policy, max_large=2)
+        assert all(r.status == 0 and len(r.step_done) == r_.steps for r, r_ in zip(res, reqs))
+        assert not ex.live
+        small_lat = [x for r in res if r.nF <= 50000 for x in r.step_latencies()]
+        lat[policy] = max(small_lat)
+        if policy is not None:
+            # no shared step mixes lanes, and a large mesh always steps alone
+            for b in ex.batches:
+                assert all(r < 2 for r in b) or all(r >= 2 for r in b)
+                assert len(b) == 1 or all(r >= 2 for r in b)
+            # one large step (0.02 s) plus one small batch bounds a small step's latency
+            assert lat[policy] < 0.02 + 0.001 + 12 * 8000 * 1e-7 + 1e-3 + 1e-9
+    assert lat[50000] < lat[None]
