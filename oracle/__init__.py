@@ -49,6 +49,9 @@ def lib():
         L.tpo_gradient_rowlist.argtypes = [_dp, i64, _ip, i64, d, d, _lp, i64, _dp, _dp]
         L.tpo_fractional_rowlist.argtypes = [_dp, i64, _ip, i64, d, _dp, ctypes.c_int, _lp, i64, _dp]
         L.tpo_fractional_gather.argtypes = [_ip, i64, i64, _dp, ctypes.c_int, _dp]
+        L.tpo_bh_frozen.argtypes = [_dp, _dp, i64, _ip, i64, d, d, d, ctypes.c_int, _dp, _lp]
+        L.tpo_bh_frozen.restype = d
+        L.tpo_bh_order.argtypes = [_dp, _ip, i64, ctypes.c_int, _lp]
         _lib = L
     return _lib
 
@@ -428,3 +431,34 @@ def _mean_edge_length(V, F) -> float:
     e = np.concatenate([F[:, [0, 1]], F[:, [1, 2]], F[:, [2, 0]]])
     e = np.unique(np.sort(e, axis=1), axis=0)
     return float(np.linalg.norm(V[e[:, 0]] - V[e[:, 1]], axis=1).mean())
+
+
+# ----------------------------------------------------------------------------------
+# Barnes-Hut approximation (Sec. 4): tree, admissibility and traversal as written in the
+# C oracle; the differential is exact for E_BH with the interaction lists held fixed.
+
+def bh_gradient(V, F, theta, leaf=8, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, with_grad=True):
+    """(E_BH, dE_BH or None, (far terms, near terms))."""
+    V, F = _prep(V, F)
+    dE = np.empty_like(V) if with_grad else None
+    cnt = np.zeros(2, dtype=np.int64)
+    E = lib().tpo_bh_frozen(_d(V), _d(V), V.shape[0], _i(F), F.shape[0], alpha, beta, float(theta),
+                            int(leaf), _d(dE) if with_grad else None,
+                            cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return float(E), dE, (int(cnt[0]), int(cnt[1]))
+
+
+def bh_energy_frozen(V0, V, F, theta, leaf=8, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
+    """E_BH at vertices V with the tree membership and interaction lists of V0."""
+    V0, F = _prep(V0, F)
+    V = np.ascontiguousarray(V, dtype=np.float64)
+    return float(lib().tpo_bh_frozen(_d(V0), _d(V), V.shape[0], _i(F), F.shape[0], alpha, beta,
+                                     float(theta), int(leaf), None, None))
+
+
+def bh_order(V, F, leaf=8):
+    """Sorted face order of the tree (Morton code of the barycenter, ties by index)."""
+    V, F = _prep(V, F)
+    out = np.empty(F.shape[0], dtype=np.int64)
+    lib().tpo_bh_order(_d(V), _i(F), F.shape[0], int(leaf), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return out

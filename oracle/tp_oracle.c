@@ -345,3 +345,338 @@ EXPORT int tpo_fractional_apply(const double* V, int64_t nV, const int32_t* F, i
     free(w);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Barnes-Hut approximation of the energy (Sec. 4.1) and its differential (Sec. 4.2).
+ *
+ * Tree (reading: the paper names a BVH with at most 8 faces per leaf and leaves the
+ * build open).  Faces are sorted by the 30-bit Morton code of their barycenter, each
+ * coordinate quantized to 10 bits on the bounding box of all barycenters
+ * (q = min(1023, floor(1024 (x - lo) / (hi - lo)))), ties broken by face index.  Leaves
+ * hold `leaf` consecutive sorted faces; the internal nodes form a perfect binary tree over
+ * the leaves in heap order (node 1 is the root, node i has children 2i and 2i + 1, the
+ * leaves are nodes P .. 2P - 1 for P the smallest power of two >= the number of leaves;
+ * the leaves past the last face are empty).  A node I carries a_I = sum of its faces'
+ * areas, X_I = (sum a_T X_T) / a_I (sums in sorted order, children left then right) and
+ * the bounding box of its faces' vertices.
+ *
+ * Admissibility (reading: the printed inequality lacks theta): node I is admissible for
+ * face S when max(r_S^2, r_I^2) < theta^2 dist^2, with r_S the largest distance from X_S
+ * to a corner of S, r_I the largest distance from X_I to a corner of the box of I and
+ * dist the distance between the box of S's vertices and the box of I.  theta = 0 admits
+ * nothing and gives the exact sum.
+ *
+ * Traversal from the root, depth first, left child first: an admissible node adds
+ * K(X_S, N_S; X_I) a_S a_I; a leaf that is not admissible adds the exact terms
+ * K(S,T) a_S a_T of its faces T != S; other nodes are opened.  E_BH is the sum over S.
+ *
+ * Differential (reading: the exact gradient of E_BH with every face's list of admissible
+ * nodes and opened leaves held fixed).  Each term w K(X_S, N_S; Y) a_S with target Y,
+ * w = a_T or a_I, gives S: dX += a_S w dK/dd, dN += a_S w dK/dN, da += w K, and the target:
+ * dY -= a_S w dK/dd, dw += a_S K.  A node's (dX_I, da_I) reach its member faces through
+ * X_I = sum a_T X_T / a_I and a_I = sum a_T:
+ *   dX_T += (a_T / a_I) dX_I,   da_T += da_I + (X_T - X_I) . dX_I / a_I.
+ * All arithmetic is FP64; sums run in face order, then node order (deterministic).       */
+
+typedef struct {
+    int64_t nF, nleaf, P;
+    int leaf;
+    int64_t* order;        /* sorted position -> face */
+    double* lo;            /* [2P][3] node boxes */
+    double* hi;
+    double* a;             /* [2P] */
+    double* X;             /* [2P][3] */
+    double* r2;            /* [2P] */
+    double* flo;           /* [nF][3] face boxes */
+    double* fhi;
+    double* fr2;           /* [nF] r_S^2 */
+} bh_tree;
+
+static uint32_t bh_spread10(uint32_t v)
+{
+    uint32_t out = 0;
+    for (int b = 0; b < 10; ++b) out |= ((v >> b) & 1u) << (3 * b);
+    return out;
+}
+
+static uint32_t bh_quant(double x, double lo, double hi)
+{
+    if (!(hi > lo)) return 0;
+    double t = floor(1024.0 * ((x - lo) / (hi - lo)));
+    if (t < 0.0) t = 0.0;
+    if (t > 1023.0) t = 1023.0;
+    return (uint32_t)t;
+}
+
+static const uint64_t* bh_sort_keys;
+static int bh_cmp(const void* pa, const void* pb)
+{
+    uint64_t ka = bh_sort_keys[*(const int64_t*)pa], kb = bh_sort_keys[*(const int64_t*)pb];
+    return ka < kb ? -1 : (ka > kb ? 1 : 0);
+}
+
+static void bh_build(const double* V, const int32_t* F, int64_t nF, const double* X, const double* A,
+                     int leaf, bh_tree* T)
+{
+    T->nF = nF;
+    T->leaf = leaf;
+    T->nleaf = (nF + leaf - 1) / leaf;
+    T->P = 1;
+    while (T->P < T->nleaf) T->P *= 2;
+    const int64_t M = 2 * T->P;
+    T->order = malloc(sizeof(int64_t) * nF);
+    T->lo = malloc(sizeof(double) * 3 * M);
+    T->hi = malloc(sizeof(double) * 3 * M);
+    T->a = calloc(M, sizeof(double));
+    T->X = calloc(3 * M, sizeof(double));
+    T->r2 = calloc(M, sizeof(double));
+    T->flo = malloc(sizeof(double) * 3 * nF);
+    T->fhi = malloc(sizeof(double) * 3 * nF);
+    T->fr2 = malloc(sizeof(double) * nF);
+    /* face boxes and r_S^2 */
+    for (int64_t s = 0; s < nF; ++s) {
+        double best = 0.0;
+        for (int m = 0; m < 3; ++m) { T->flo[3 * s + m] = INFINITY; T->fhi[3 * s + m] = -INFINITY; }
+        for (int c = 0; c < 3; ++c) {
+            const double* v = V + 3 * (int64_t)F[3 * s + c];
+            double d2 = 0.0;
+            for (int m = 0; m < 3; ++m) {
+                if (v[m] < T->flo[3 * s + m]) T->flo[3 * s + m] = v[m];
+                if (v[m] > T->fhi[3 * s + m]) T->fhi[3 * s + m] = v[m];
+                double dm = v[m] - X[3 * s + m];
+                d2 += dm * dm;
+            }
+            if (d2 > best) best = d2;
+        }
+        T->fr2[s] = best;
+    }
+    /* Morton order */
+    double blo[3] = {INFINITY, INFINITY, INFINITY}, bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t s = 0; s < nF; ++s)
+        for (int m = 0; m < 3; ++m) {
+            if (X[3 * s + m] < blo[m]) blo[m] = X[3 * s + m];
+            if (X[3 * s + m] > bhi[m]) bhi[m] = X[3 * s + m];
+        }
+    uint64_t* key = malloc(sizeof(uint64_t) * nF);
+    for (int64_t s = 0; s < nF; ++s) {
+        uint32_t code = (bh_spread10(bh_quant(X[3 * s], blo[0], bhi[0])) << 2) |
+                        (bh_spread10(bh_quant(X[3 * s + 1], blo[1], bhi[1])) << 1) |
+                        bh_spread10(bh_quant(X[3 * s + 2], blo[2], bhi[2]));
+        key[s] = ((uint64_t)code << 32) | (uint64_t)s;
+        T->order[s] = s;
+    }
+    bh_sort_keys = key;
+    qsort(T->order, nF, sizeof(int64_t), bh_cmp);
+    free(key);
+    /* leaves */
+    for (int64_t i = 0; i < M; ++i)
+        for (int m = 0; m < 3; ++m) { T->lo[3 * i + m] = INFINITY; T->hi[3 * i + m] = -INFINITY; }
+    double* sx = calloc(3 * M, sizeof(double));
+    for (int64_t l = 0; l < T->P; ++l) {
+        const int64_t node = T->P + l;
+        for (int64_t p = l * leaf; p < (l + 1) * leaf && p < nF; ++p) {
+            const int64_t s = T->order[p];
+            T->a[node] += A[s];
+            for (int m = 0; m < 3; ++m) {
+                sx[3 * node + m] += A[s] * X[3 * s + m];
+                if (T->flo[3 * s + m] < T->lo[3 * node + m]) T->lo[3 * node + m] = T->flo[3 * s + m];
+                if (T->fhi[3 * s + m] > T->hi[3 * node + m]) T->hi[3 * node + m] = T->fhi[3 * s + m];
+            }
+        }
+    }
+    for (int64_t node = T->P - 1; node >= 1; --node) {
+        const int64_t L = 2 * node, R = 2 * node + 1;
+        T->a[node] = T->a[L] + T->a[R];
+        for (int m = 0; m < 3; ++m) {
+            sx[3 * node + m] = sx[3 * L + m] + sx[3 * R + m];
+            T->lo[3 * node + m] = T->lo[3 * L + m] < T->lo[3 * R + m] ? T->lo[3 * L + m] : T->lo[3 * R + m];
+            T->hi[3 * node + m] = T->hi[3 * L + m] > T->hi[3 * R + m] ? T->hi[3 * L + m] : T->hi[3 * R + m];
+        }
+    }
+    for (int64_t node = 1; node < M; ++node) {
+        if (!(T->a[node] > 0.0)) continue;
+        double r2 = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            T->X[3 * node + m] = sx[3 * node + m] / T->a[node];
+            double u = T->X[3 * node + m] - T->lo[3 * node + m];
+            double v = T->hi[3 * node + m] - T->X[3 * node + m];
+            double w = u > v ? u : v;
+            r2 += w * w;
+        }
+        T->r2[node] = r2;
+    }
+    free(sx);
+}
+
+static void bh_free(bh_tree* T)
+{
+    free(T->order); free(T->lo); free(T->hi); free(T->a); free(T->X); free(T->r2);
+    free(T->flo); free(T->fhi); free(T->fr2);
+}
+
+static int bh_admissible(const bh_tree* T, int64_t s, int64_t node, double theta)
+{
+    double d2 = 0.0;
+    for (int m = 0; m < 3; ++m) {
+        double g1 = T->lo[3 * node + m] - T->fhi[3 * s + m];
+        double g2 = T->flo[3 * s + m] - T->hi[3 * node + m];
+        double g = g1 > g2 ? g1 : g2;
+        if (g < 0.0) g = 0.0;
+        d2 += g * g;
+    }
+    double r2 = T->fr2[s] > T->r2[node] ? T->fr2[s] : T->r2[node];
+    return r2 < (theta * theta) * d2;
+}
+
+/* One face's interaction list, in traversal order: kinds[q] = 0 for a node, 1 for a face,
+ * ids[q] its index.  Returns the count; the arrays are grown as needed. */
+static int64_t bh_list(const bh_tree* T, int64_t s, double theta, int** kinds, int64_t** ids, int64_t* cap)
+{
+    int64_t n = 0;
+    int64_t stack[128];
+    int sp = 0;
+    stack[sp++] = 1;
+    while (sp > 0) {
+        const int64_t node = stack[--sp];
+        if (!(T->a[node] > 0.0)) continue;
+        int leafnode = node >= T->P;
+        if (n + T->leaf + 1 > *cap) {
+            *cap = 2 * (*cap) + T->leaf + 1;
+            *kinds = realloc(*kinds, sizeof(int) * (*cap));
+            *ids = realloc(*ids, sizeof(int64_t) * (*cap));
+        }
+        if (bh_admissible(T, s, node, theta)) {
+            (*kinds)[n] = 0; (*ids)[n] = node; ++n;
+        } else if (leafnode) {
+            const int64_t l = node - T->P;
+            for (int64_t p = l * T->leaf; p < (l + 1) * T->leaf && p < T->nF; ++p) {
+                const int64_t t = T->order[p];
+                if (t == s) continue;
+                (*kinds)[n] = 1; (*ids)[n] = t; ++n;
+            }
+        } else {
+            stack[sp++] = 2 * node + 1;      /* right popped after left */
+            stack[sp++] = 2 * node;
+        }
+    }
+    return n;
+}
+
+/* E_BH and (optionally) its differential at vertices V, with the tree membership and the
+ * interaction lists taken from vertices V0 (V0 = V for the plain evaluation; a different V
+ * evaluates E_BH with the lists frozen, for finite differences).  counts[0] = far terms,
+ * counts[1] = near terms (over all faces). */
+EXPORT double tpo_bh_frozen(const double* V0, const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                            double alpha, double beta, double theta, int leaf, double* dE,
+                            int64_t* counts)
+{
+    double* X0 = calloc(3 * nF, sizeof(double));
+    double* N0 = calloc(3 * nF, sizeof(double));
+    double* A0 = calloc(nF, sizeof(double));
+    double* C0 = calloc(3 * nF, sizeof(double));
+    all_faces(V0, F, nF, X0, N0, A0, C0);
+    bh_tree T;
+    bh_build(V0, F, nF, X0, A0, leaf, &T);
+    /* quantities at V (same membership) */
+    double* X = malloc(sizeof(double) * 3 * nF);
+    double* N = malloc(sizeof(double) * 3 * nF);
+    double* A = malloc(sizeof(double) * nF);
+    double* C = malloc(sizeof(double) * 3 * nF);
+    all_faces(V, F, nF, X, N, A, C);
+    const int64_t M = 2 * T.P;
+    double* na = calloc(M, sizeof(double));
+    double* nX = calloc(3 * M, sizeof(double));
+    {
+        double* sx = calloc(3 * M, sizeof(double));
+        for (int64_t l = 0; l < T.P; ++l)
+            for (int64_t p = l * leaf; p < (l + 1) * leaf && p < nF; ++p) {
+                const int64_t s = T.order[p];
+                na[T.P + l] += A[s];
+                for (int m = 0; m < 3; ++m) sx[3 * (T.P + l) + m] += A[s] * X[3 * s + m];
+            }
+        for (int64_t node = T.P - 1; node >= 1; --node) {
+            na[node] = na[2 * node] + na[2 * node + 1];
+            for (int m = 0; m < 3; ++m) sx[3 * node + m] = sx[3 * (2 * node) + m] + sx[3 * (2 * node + 1) + m];
+        }
+        for (int64_t node = 1; node < M; ++node)
+            if (na[node] > 0.0)
+                for (int m = 0; m < 3; ++m) nX[3 * node + m] = sx[3 * node + m] / na[node];
+        free(sx);
+    }
+    double* gface = dE ? calloc(7 * nF, sizeof(double)) : NULL;
+    double* gnode = dE ? calloc(4 * M, sizeof(double)) : NULL;
+    int* kinds = NULL;
+    int64_t* ids = NULL;
+    int64_t cap = 0, nfar = 0, nnear = 0;
+    double E = 0.0;
+    for (int64_t s = 0; s < nF; ++s) {
+        const int64_t n = bh_list(&T, s, theta, &kinds, &ids, &cap);
+        double row = 0.0;
+        for (int64_t q = 0; q < n; ++q) {
+            const int far = kinds[q] == 0;
+            const int64_t id = ids[q];
+            const double* Y = far ? nX + 3 * id : X + 3 * id;
+            const double w = far ? na[id] : A[id];
+            far ? ++nfar : ++nnear;
+            double dKdd[3], dKdN[3];
+            const double K = tp_kernel_grad(X + 3 * s, N + 3 * s, Y, alpha, beta, dKdd, dKdN);
+            row += K * A[s] * w;
+            if (!dE) continue;
+            double* gs = gface + 7 * s;
+            for (int m = 0; m < 3; ++m) {
+                gs[m] += A[s] * w * dKdd[m];
+                gs[3 + m] += A[s] * w * dKdN[m];
+            }
+            gs[6] += w * K;
+            if (far) {
+                double* gn = gnode + 4 * id;
+                for (int m = 0; m < 3; ++m) gn[m] -= A[s] * w * dKdd[m];
+                gn[3] += A[s] * K;
+            } else {
+                double* gt = gface + 7 * id;
+                for (int m = 0; m < 3; ++m) gt[m] -= A[s] * w * dKdd[m];
+                gt[6] += A[s] * K;
+            }
+        }
+        E += row;
+    }
+    if (dE) {
+        /* node derivatives to member faces */
+        for (int64_t l = 0; l < T.P; ++l)
+            for (int64_t p = l * leaf; p < (l + 1) * leaf && p < nF; ++p) {
+                const int64_t t = T.order[p];
+                for (int64_t node = T.P + l; node >= 1; node /= 2) {
+                    if (!(na[node] > 0.0)) continue;
+                    const double* gn = gnode + 4 * node;
+                    double proj = 0.0;
+                    for (int m = 0; m < 3; ++m) {
+                        gface[7 * t + m] += (A[t] / na[node]) * gn[m];
+                        proj += (X[3 * t + m] - nX[3 * node + m]) * gn[m];
+                    }
+                    gface[7 * t + 6] += gn[3] + proj / na[node];
+                }
+            }
+        tpo_face_to_vertex(V, nV, F, nF, gface, dE);
+        free(gface); free(gnode);
+    }
+    if (counts) { counts[0] = nfar; counts[1] = nnear; }
+    free(kinds); free(ids); free(na); free(nX);
+    free(X0); free(N0); free(A0); free(C0); free(X); free(N); free(A); free(C);
+    bh_free(&T);
+    return E;
+}
+
+/* The sorted face order of the tree (for checks of the build). */
+EXPORT void tpo_bh_order(const double* V, const int32_t* F, int64_t nF, int leaf, int64_t* order)
+{
+    double* X = malloc(sizeof(double) * 3 * nF);
+    double* N = malloc(sizeof(double) * 3 * nF);
+    double* A = malloc(sizeof(double) * nF);
+    double* C = malloc(sizeof(double) * 3 * nF);
+    all_faces(V, F, nF, X, N, A, C);
+    bh_tree T;
+    bh_build(V, F, nF, X, A, leaf, &T);
+    memcpy(order, T.order, sizeof(int64_t) * nF);
+    bh_free(&T);
+    free(X); free(N); free(A); free(C);
+}
