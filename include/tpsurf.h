@@ -81,6 +81,10 @@ typedef struct {
     int    cg_precond;   /* 1: two-level additive Schwarz preconditioner (default, used
                             when the mesh has at most 256 blocks of 128 vertices);
                             0: unpreconditioned CG                                        */
+    double theta;        /* 0 (default): E and dE by the direct all-pairs sums; > 0: the
+                            Barnes-Hut approximation of Sec. 4 with opening parameter
+                            theta (the paper's default is 0.5), see tp_problem_bh_stats  */
+    int    leaf_size;    /* faces per Barnes-Hut leaf, 1..64, default 8 (Sec. 4.1)       */
 } tp_params;
 
 /* Fill *p with the defaults above. */
@@ -223,6 +227,19 @@ TP_API tp_status tp_problem_device_bytes(const tp_problem* prob, uint64_t* bytes
 TP_API tp_status tp_estimate_device_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp,
                                           const tp_params* params, int n_constraints,
                                           uint64_t* bytes);
+
+/* Barnes-Hut (params.theta > 0): E and dE of every energy / gradient / step call of the
+ * problem use E_BH (Sec. 4.1): faces sorted by the Morton code of their barycenters (10
+ * bits per coordinate on the barycenters' bounding box, ties by face index), leaves of
+ * leaf_size consecutive faces, a perfect binary tree over the leaves; node I is
+ * admissible for face S when max(r_S^2, r_I^2) < theta^2 dist^2 (r_S: largest distance
+ * from X_S to a corner of S, r_I: from X_I = area-weighted barycenter to a corner of I's
+ * box, dist: distance between the vertex boxes of S and I); admissible nodes contribute
+ * K(X_S, N_S; X_I) a_S a_I, opened leaves their exact terms.  dE is the exact differential
+ * of E_BH with the interaction lists held fixed (Sec. 4.2).  The fractional apply and the
+ * Poisson solves are unchanged.  This call reports the numbers of far (node) and near
+ * (face) terms of the problem's last Barnes-Hut evaluation. */
+TP_API tp_status tp_problem_bh_stats(tp_problem* prob, int64_t* far_terms, int64_t* near_terms);
 
 /* ------------------------------------------------------------------- diagnostics */
 

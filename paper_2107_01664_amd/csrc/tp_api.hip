@@ -247,6 +247,16 @@ struct tp_problem {
     DevBuf<int> cg_iters;
     DevBuf<double> R, Y, W1, W2, gbuf, dir, Vt, Vsave;
 
+    // Barnes-Hut tree and work arrays (params.theta > 0)
+    DevBuf<double> bh_flo, bh_fhi, bh_fr2, bh_box, bh_na, bh_nsx, bh_nX, bh_nlo, bh_nhi, bh_nr2, bh_gS, bh_eS,
+        bh_accF, bh_accN;
+    DevBuf<uint64_t> bh_kin, bh_kout;
+    DevBuf<char> bh_tmp;
+    DevBuf<int32_t> bh_order, bh_pos;
+    DevBuf<unsigned long long> bh_counts;
+    BhBuffers bh;
+    const double* fd_V = nullptr;    // vertices the face data currently describe
+
     // pinned host mirrors of device scalars, flags and CG results; multi-problem CG tables
     HostBuf<double> hs, hrelres;
     HostBuf<int> hflags, hiters;
@@ -270,6 +280,10 @@ struct tp_problem {
              cg_iters.bytes();
         b += R.bytes() + Y.bytes() + W1.bytes() + W2.bytes() + gbuf.bytes() + dir.bytes() + Vt.bytes() +
              Vsave.bytes() + tab.dev.bytes();
+        b += bh_flo.bytes() + bh_fhi.bytes() + bh_fr2.bytes() + bh_box.bytes() + bh_na.bytes() + bh_nsx.bytes() +
+             bh_nX.bytes() + bh_nlo.bytes() + bh_nhi.bytes() + bh_nr2.bytes() + bh_gS.bytes() + bh_eS.bytes() +
+             bh_accF.bytes() + bh_accN.bytes() + bh_kin.bytes() + bh_kout.bytes() + bh_tmp.bytes() +
+             bh_order.bytes() + bh_pos.bytes() + bh_counts.bytes();
         return b;
     }
 };
@@ -304,6 +318,8 @@ tp_status validate_params(const tp_params* in, tp_params& out, double& sigma)
     if (!(out.cg_rtol > 0.0)) return fail(TP_E_INVALID_ARGUMENT, "cg_rtol must be > 0");
     if (out.cg_maxiter < 1) return fail(TP_E_INVALID_ARGUMENT, "cg_maxiter must be >= 1");
     if (out.cg_precond != 0 && out.cg_precond != 1) return fail(TP_E_INVALID_ARGUMENT, "cg_precond must be 0 or 1");
+    if (!(out.theta >= 0.0) || !std::isfinite(out.theta)) return fail(TP_E_INVALID_ARGUMENT, "theta must be finite and >= 0");
+    if (out.leaf_size < 1 || out.leaf_size > 64) return fail(TP_E_INVALID_ARGUMENT, "leaf_size must lie in [1, 64]");
     sigma = out.sigma;
     if (sigma < 0.0) {
         const double s = (out.beta - 2.0) / out.alpha;   // s = 2 - 2/p when beta = 2 alpha
@@ -368,6 +384,7 @@ tp_status geometry(tp_problem* P, const double* Vsrc = nullptr)
     TP_HIP(launch_face_geom(src, P->nV, P->F.p, P->nF, P->fd, P->flags.p, P->stream));
     TP_TRY(check_flags(P));
     P->geom_valid = (Vsrc == nullptr);
+    P->fd_V = src;
     return TP_OK;
 }
 
@@ -677,12 +694,80 @@ tp_status flag_status(tp_problem* P)
     return TP_OK;
 }
 
+// ------------------------------------------------------------------ Barnes-Hut
+
+tp_status ensure_bh(tp_problem* P)
+{
+    hipStream_t s = P->stream;
+    const int64_t nF = P->nF;
+    const int64_t M = (int64_t)bh_node_count(nF, P->prm.leaf_size, nullptr);
+    TP_TRY(P->bh_flo.ensure(3 * nF, s));
+    TP_TRY(P->bh_fhi.ensure(3 * nF, s));
+    TP_TRY(P->bh_fr2.ensure(nF, s));
+    TP_TRY(P->bh_box.ensure(6, s));
+    TP_TRY(P->bh_kin.ensure(nF, s));
+    TP_TRY(P->bh_kout.ensure(nF, s));
+    const size_t tb = bh_sort_temp_bytes(nF);
+    TP_TRY(P->bh_tmp.ensure(tb, s));
+    TP_TRY(P->bh_order.ensure(nF, s));
+    TP_TRY(P->bh_pos.ensure(nF, s));
+    TP_TRY(P->bh_na.ensure(M, s));
+    TP_TRY(P->bh_nsx.ensure(3 * M, s));
+    TP_TRY(P->bh_nX.ensure(3 * M, s));
+    TP_TRY(P->bh_nlo.ensure(3 * M, s));
+    TP_TRY(P->bh_nhi.ensure(3 * M, s));
+    TP_TRY(P->bh_nr2.ensure(M, s));
+    TP_TRY(P->bh_gS.ensure(7 * nF, s));
+    TP_TRY(P->bh_eS.ensure(nF, s));
+    TP_TRY(P->bh_accF.ensure(4 * nF, s));
+    TP_TRY(P->bh_accN.ensure(4 * M, s));
+    TP_TRY(P->bh_counts.ensure(2, s));
+    BhBuffers& b = P->bh;
+    b.flo = P->bh_flo.p; b.fhi = P->bh_fhi.p; b.fr2 = P->bh_fr2.p; b.box = P->bh_box.p;
+    b.keys_in = P->bh_kin.p; b.keys_out = P->bh_kout.p; b.sort_tmp = P->bh_tmp.p; b.sort_bytes = tb;
+    b.order = P->bh_order.p; b.pos = P->bh_pos.p; b.na = P->bh_na.p; b.nsx = P->bh_nsx.p; b.nX = P->bh_nX.p;
+    b.nlo = P->bh_nlo.p; b.nhi = P->bh_nhi.p; b.nr2 = P->bh_nr2.p; b.gS = P->bh_gS.p; b.eS = P->bh_eS.p;
+    b.accF = P->bh_accF.p; b.accN = P->bh_accN.p; b.counts = P->bh_counts.p;
+    return TP_OK;
+}
+
+// E_BH -> scal[slot]; with dE, the differential of E_BH into dE (nV x 3).  The face data
+// must describe P->fd_V (the tree is built from it).
+tp_status enqueue_bh(tp_problem* P, double* dE, int slot)
+{
+    hipStream_t s = P->stream;
+    TP_TRY(ensure_bh(P));
+    const int leaf = P->prm.leaf_size;
+    TP_HIP(launch_bh_build(P->bh, P->fd_V, P->F.p, P->nF, leaf, P->fd, s));
+    if (dE) {
+        TP_TRY(ensure_vf(P));
+        TP_TRY(P->gface.ensure((size_t)7 * P->nF, s));
+    }
+    TP_HIP(launch_bh_eval(P->bh, P->nF, leaf, P->prm.theta, P->prm.precision, P->prm.alpha, P->prm.beta, P->fd,
+                          dE != nullptr, P->gface.p, P->nF, s));
+    if (dE)
+        TP_HIP(launch_grad_gather(P->fd_V, P->F.p, P->nV, P->nF, P->vf_off.p, P->vf_idx.p, P->gface.p, P->nF, dE, s));
+    TP_HIP(launch_dot_cols(P->bh_eS.p, 1, nullptr, 0, P->nF, 1, P->red.p, P->scal.p + slot, s));
+    return TP_OK;
+}
+
+// The energy from the scalar the gradient phase leaves in its slot: twice the energy for
+// the direct sums (sum_S a_S dE/da_S), E_BH itself for Barnes-Hut.
+double gradient_energy(const tp_problem* P, double v)
+{
+    return P->prm.theta > 0.0 ? v : 0.5 * v;
+}
+
 // ------------------------------------------------------------------ all-pairs phases
 
 // E of every problem (face data must describe the point of evaluation) -> scal[slot].
 tp_status enqueue_energy(const Batch& B, int slot)
 {
     if (B.empty()) return TP_OK;
+    if (B[0]->prm.theta > 0.0) {
+        for (tp_problem* P : B) TP_TRY(enqueue_bh(P, nullptr, slot));
+        return TP_OK;
+    }
     hipStream_t s = B[0]->stream;
     const int prec = B[0]->prm.precision;
     std::vector<PairJob> jobs;
@@ -715,6 +800,10 @@ tp_status enqueue_energy(const Batch& B, int slot)
 tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
 {
     if (B.empty()) return TP_OK;
+    if (B[0]->prm.theta > 0.0) {
+        for (size_t m = 0; m < B.size(); ++m) TP_TRY(enqueue_bh(B[m], dE[m], slot));
+        return TP_OK;
+    }
     hipStream_t s = B[0]->stream;
     const int prec = B[0]->prm.precision;
     std::vector<PairJob> jobs;
@@ -991,7 +1080,7 @@ tp_status run_gradient(tp_problem* P, double* E, double* dE)
     TP_TRY(enqueue_fetch(B));
     TP_TRY(sync_batch(B));
     TP_TRY(flag_status(P));
-    *E = 0.5 * P->hs.p[kSlotE];
+    *E = gradient_energy(P, P->hs.p[kSlotE]);
     if (!finite(*E)) return fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
     return TP_OK;
 }
@@ -1231,7 +1320,7 @@ tp_status step_group(std::vector<StepState*>& G)
         const tp_status c2 = cg_result(P, ncol, 1, &S->R.cg_iters[1], &S->R.cg_relres[1]);
         if (c1 != TP_OK) S->st = c1;
         else if (c2 != TP_OK) S->st = c2;
-        S->E0 = 0.5 * h[kSlotE];
+        S->E0 = gradient_energy(P, h[kSlotE]);
         if (!finite(S->E0)) {
             S->st = fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
             continue;
@@ -1304,6 +1393,7 @@ tp_status step_group(std::vector<StepState*>& G)
             const int c0 = 0;
             TP_HIP(launch_axpy_block3(P->nV, P->V.p, 3, 1.0, P->dir.p, 3, 1, &cf, &c0, P->Vt.p, 3, s));
             TP_HIP(launch_face_geom(P->Vt.p, P->nV, P->F.p, P->nF, P->fd, P->flags.p, s));
+            P->fd_V = P->Vt.p;
             P->geom_valid = false;
             BS.push_back(P);
         }
@@ -1370,6 +1460,7 @@ tp_status step_group(std::vector<StepState*>& G)
             TP_HIP(hipMemcpyAsync(S->dir_out, P->dir.p, sizeof(double) * 3 * P->nV, hipMemcpyDeviceToDevice, s));
         P->cotan_valid = false;
         TP_HIP(launch_face_geom(P->V.p, P->nV, P->F.p, P->nF, P->fd, P->flags.p, s));
+        P->fd_V = P->V.p;
         TP_TRY(enqueue_area_volume(P, P->V.p));
         BF.push_back(P);
         fin.push_back(S);
@@ -1452,7 +1543,8 @@ tp_status run_step_batch(tp_problem* const* probs, int n, const tp_step_opts* op
             const tp_problem* a = S[m].P;
             const tp_problem* b = S[q].P;
             if (a->prm.precision == b->prm.precision && a->prm.alpha == b->prm.alpha &&
-                a->prm.beta == b->prm.beta && a->sigma == b->sigma && S[m].ncol == S[q].ncol) {
+                a->prm.beta == b->prm.beta && a->sigma == b->sigma && S[m].ncol == S[q].ncol &&
+                a->prm.theta == b->prm.theta && a->prm.leaf_size == b->prm.leaf_size) {
                 G.push_back(&S[q]);
                 done[q] = true;
             }
@@ -1508,6 +1600,11 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
     b += 8 * part + 8 * gface + 8.0 * kf * pf.irows + (double)cap * ((kf + 3) / 4 * 4) * esz;
     // step work arrays, per-face volumes and edge lengths, CG tables
     b += 8 * n * ncol * 4 + 8 * n * 3 * 3 + 16 * f + 4096;
+    // Barnes-Hut tree, keys, sort scratch and per-face sums
+    if (prm.theta > 0.0) {
+        const double M = (double)bh_node_count(nF, prm.leaf_size, nullptr);
+        b += f * (176.0 + 56.0) + M * 144.0 + (double)bh_sort_temp_bytes(nF) + 64;
+    }
     return (uint64_t)(b * 1.02) + 65536;
 }
 
@@ -1542,6 +1639,8 @@ tp_status tp_params_default(tp_params* p)
     p->cg_rtol = 1e-10;
     p->cg_maxiter = 20000;
     p->cg_precond = 1;
+    p->theta = 0.0;
+    p->leaf_size = 8;
     return TP_OK;
 }
 
@@ -1728,6 +1827,8 @@ tp_status tp_energy_faces(const double* X, const double* N, const double* a, int
     ProblemGuard g;
     g.p = P;
     TP_TRY(validate_params(params, P->prm, P->sigma));
+    if (P->prm.theta > 0.0)
+        return fail(TP_E_INVALID_ARGUMENT, "Barnes-Hut (theta > 0) needs the mesh: use tp_energy or a problem");
     (void)hipGetDevice(&P->device);
     P->stream = (hipStream_t)stream;
     P->nF = nF;
@@ -1736,6 +1837,20 @@ tp_status tp_energy_faces(const double* X, const double* N, const double* a, int
     TP_HIP(launch_face_from_quantities(X, N, a, nF, P->fd, P->flags.p, P->stream));
     TP_TRY(check_flags(P));
     return run_energy(P, E_out);
+}
+
+tp_status tp_problem_bh_stats(tp_problem* P, int64_t* far_terms, int64_t* near_terms)
+{
+    TP_TRY(bind(P));
+    if (!far_terms || !near_terms) return fail(TP_E_INVALID_ARGUMENT, "NULL argument");
+    unsigned long long h[2] = {0, 0};
+    if (P->bh_counts.p) {
+        TP_HIP(hipMemcpyAsync(h, P->bh_counts.p, sizeof(h), hipMemcpyDeviceToHost, P->stream));
+        TP_HIP(hipStreamSynchronize(P->stream));
+    }
+    *far_terms = (int64_t)h[0];
+    *near_terms = (int64_t)h[1];
+    return TP_OK;
 }
 
 tp_status tp_problem_device_bytes(const tp_problem* P, uint64_t* bytes)

@@ -1,0 +1,475 @@
+// Barnes-Hut approximation of the energy and its differential (Sec. 4) on gfx950.
+//
+// Tree.  Faces are sorted by the 30-bit Morton code of their barycenters (10 bits per
+// coordinate, quantized on the bounding box of all barycenters; ties by face index, so
+// the 64-bit keys code << 32 | face are unique).  Leaves hold `leaf` consecutive sorted
+// faces and the internal nodes form a perfect binary tree over the leaves in heap order
+// (node 1 is the root, node i has children 2i and 2i + 1, the leaves are nodes
+// P .. 2P - 1).  The tree is therefore fixed by the sort alone: no pointer chasing, and
+// the traversal needs no stack (the next node after a subtree follows from the heap
+// index).  Node quantities are built level by level: a_I, sum a_T X_T, the bounding box of
+// the faces' vertices, X_I and r_I^2 (largest squared distance from X_I to a box corner).
+// The geometric quantities that decide admissibility are formed in FP64 without fused
+// multiply-adds, in a fixed order, so the interaction lists are a function of the mesh.
+//
+// Admissibility: node I is admissible for face S when max(r_S^2, r_I^2) < theta^2 dist^2
+// (r_S: largest distance from X_S to a corner of S; dist: distance between the box of S's
+// vertices and the box of I).
+//
+// Traversal.  One thread per face, threads in Morton order so the lanes of a wave walk
+// similar paths.  An admissible node adds K(X_S, N_S; X_I) a_S a_I, a leaf that is not
+// admissible adds the exact terms of its faces T != S, other nodes are opened.  The
+// differential is that of E_BH with the lists held fixed: the face S side is summed per
+// thread; the target side (dX, da of a face T or a node I) is added with device-scope
+// atomics; node derivatives then reach their member faces through X_I = sum a_T X_T / a_I
+// and a_I = sum a_T, walking up each face's ancestors.  The atomic sums make the last bits
+// of dE depend on scheduling; E itself is summed per face in a fixed order.
+#include "tp_internal.h"
+
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+
+namespace tp {
+
+namespace {
+
+#pragma clang fp contract(off)
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v)
+{
+    uint32_t out = 0;
+    for (int b = 0; b < 10; ++b) out |= ((v >> b) & 1u) << (3 * b);
+    return out;
+}
+
+__device__ __forceinline__ uint32_t quant10(double x, double lo, double hi)
+{
+    if (!(hi > lo)) return 0u;
+    double t = floor(1024.0 * ((x - lo) / (hi - lo)));
+    t = t < 0.0 ? 0.0 : (t > 1023.0 ? 1023.0 : t);
+    return (uint32_t)t;
+}
+
+// Face boxes (of the three vertices) and r_S^2.
+__global__ void k_bh_faceprep(const double* __restrict__ V, const int32_t* __restrict__ F, int64_t nF,
+                              const double4* __restrict__ dx, double* __restrict__ flo,
+                              double* __restrict__ fhi, double* __restrict__ fr2)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nF) return;
+    const double4 X = dx[s];
+    const double xs[3] = {X.x, X.y, X.z};
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double best = 0.0;
+    for (int c = 0; c < 3; ++c) {
+        const double* v = V + 3 * (int64_t)F[3 * s + c];
+        double d2 = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            lo[m] = v[m] < lo[m] ? v[m] : lo[m];
+            hi[m] = v[m] > hi[m] ? v[m] : hi[m];
+            const double dm = v[m] - xs[m];
+            d2 = d2 + dm * dm;
+        }
+        best = d2 > best ? d2 : best;
+    }
+    for (int m = 0; m < 3; ++m) {
+        flo[3 * s + m] = lo[m];
+        fhi[3 * s + m] = hi[m];
+    }
+    fr2[s] = best;
+}
+
+// Bounding box of the barycenters (one workgroup; min and max do not depend on order).
+__global__ __launch_bounds__(1024) void k_bh_bbox(const double4* __restrict__ dx, int64_t nF,
+                                                  double* __restrict__ box)
+{
+    __shared__ double sh[6][1024];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t s = threadIdx.x; s < nF; s += blockDim.x) {
+        const double4 X = dx[s];
+        const double x[3] = {X.x, X.y, X.z};
+        for (int m = 0; m < 3; ++m) {
+            lo[m] = x[m] < lo[m] ? x[m] : lo[m];
+            hi[m] = x[m] > hi[m] ? x[m] : hi[m];
+        }
+    }
+    for (int m = 0; m < 3; ++m) {
+        sh[m][threadIdx.x] = lo[m];
+        sh[3 + m][threadIdx.x] = hi[m];
+    }
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int m = 0; m < 3; ++m) {
+                const double a = sh[m][threadIdx.x + w], b = sh[3 + m][threadIdx.x + w];
+                sh[m][threadIdx.x] = a < sh[m][threadIdx.x] ? a : sh[m][threadIdx.x];
+                sh[3 + m][threadIdx.x] = b > sh[3 + m][threadIdx.x] ? b : sh[3 + m][threadIdx.x];
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) box[threadIdx.x] = sh[threadIdx.x][0];
+}
+
+__global__ void k_bh_keys(const double4* __restrict__ dx, int64_t nF, const double* __restrict__ box,
+                          uint64_t* __restrict__ keys)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nF) return;
+    const double4 X = dx[s];
+    const uint32_t code = (spread10(quant10(X.x, box[0], box[3])) << 2) |
+                          (spread10(quant10(X.y, box[1], box[4])) << 1) |
+                          spread10(quant10(X.z, box[2], box[5]));
+    keys[s] = ((uint64_t)code << 32) | (uint64_t)s;
+}
+
+__global__ void k_bh_order(const uint64_t* __restrict__ keys, int64_t nF, int32_t* __restrict__ order,
+                           int32_t* __restrict__ pos)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nF) return;
+    const int32_t s = (int32_t)(keys[p] & 0xffffffffull);
+    order[p] = s;
+    pos[s] = (int32_t)p;
+}
+
+// Leaf nodes P + l: sums over the member faces in sorted order.
+__global__ void k_bh_leaves(int64_t nF, int leaf, int64_t P, const int32_t* __restrict__ order,
+                            const double4* __restrict__ dx, const double* __restrict__ flo,
+                            const double* __restrict__ fhi, double* __restrict__ na,
+                            double* __restrict__ nsx, double* __restrict__ nlo, double* __restrict__ nhi)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= P) return;
+    const int64_t node = P + l;
+    double a = 0.0, sx[3] = {0.0, 0.0, 0.0};
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int64_t p = l * leaf; p < (l + 1) * leaf && p < nF; ++p) {
+        const int32_t s = order[p];
+        const double4 X = dx[s];
+        const double x[3] = {X.x, X.y, X.z};
+        a = a + X.w;
+        for (int m = 0; m < 3; ++m) {
+            sx[m] = sx[m] + X.w * x[m];
+            lo[m] = flo[3 * s + m] < lo[m] ? flo[3 * s + m] : lo[m];
+            hi[m] = fhi[3 * s + m] > hi[m] ? fhi[3 * s + m] : hi[m];
+        }
+    }
+    na[node] = a;
+    for (int m = 0; m < 3; ++m) {
+        nsx[3 * node + m] = sx[m];
+        nlo[3 * node + m] = lo[m];
+        nhi[3 * node + m] = hi[m];
+    }
+}
+
+// Internal nodes [n0, n1) from their children.
+__global__ void k_bh_level(int64_t n0, int64_t n1, double* __restrict__ na, double* __restrict__ nsx,
+                           double* __restrict__ nlo, double* __restrict__ nhi)
+{
+    const int64_t node = n0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= n1) return;
+    const int64_t L = 2 * node, R = 2 * node + 1;
+    na[node] = na[L] + na[R];
+    for (int m = 0; m < 3; ++m) {
+        nsx[3 * node + m] = nsx[3 * L + m] + nsx[3 * R + m];
+        nlo[3 * node + m] = nlo[3 * L + m] < nlo[3 * R + m] ? nlo[3 * L + m] : nlo[3 * R + m];
+        nhi[3 * node + m] = nhi[3 * L + m] > nhi[3 * R + m] ? nhi[3 * L + m] : nhi[3 * R + m];
+    }
+}
+
+__global__ void k_bh_nodefinish(int64_t M, const double* __restrict__ na, const double* __restrict__ nsx,
+                                const double* __restrict__ nlo, const double* __restrict__ nhi,
+                                double* __restrict__ nX, double* __restrict__ nr2)
+{
+    const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (node >= M || node == 0) return;
+    const double a = na[node];
+    if (!(a > 0.0)) {
+        nr2[node] = 0.0;
+        for (int m = 0; m < 3; ++m) nX[3 * node + m] = 0.0;
+        return;
+    }
+    double r2 = 0.0;
+    for (int m = 0; m < 3; ++m) {
+        const double x = nsx[3 * node + m] / a;
+        nX[3 * node + m] = x;
+        const double u = x - nlo[3 * node + m], v = nhi[3 * node + m] - x;
+        const double w = u > v ? u : v;
+        r2 = r2 + w * w;
+    }
+    nr2[node] = r2;
+}
+
+#pragma clang fp contract(fast)
+
+struct BhArgs {
+    int64_t nF, P;
+    int leaf;
+    double theta2;
+    double alpha, beta;
+    const int32_t* order;
+    const double4* dx;
+    const double4* dn;
+    const double* flo;
+    const double* fhi;
+    const double* fr2;
+    const double* na;
+    const double* nX;
+    const double* nlo;
+    const double* nhi;
+    const double* nr2;
+    double* gS;           // [7][nF] face-side sums (gradient only)
+    double* eS;           // [nF] energy rows
+    double* accF;         // [4][nF] target-side sums of faces
+    double* accN;         // [4][2P] target-side sums of nodes
+    unsigned long long* counts;   // far, near
+};
+
+__device__ __forceinline__ bool admissible(const BhArgs& A, const double (&slo)[3], const double (&shi)[3],
+                                           double sr2, int64_t node)
+{
+#pragma clang fp contract(off)
+    double d2 = 0.0;
+    for (int m = 0; m < 3; ++m) {
+        const double g1 = A.nlo[3 * node + m] - shi[m];
+        const double g2 = slo[m] - A.nhi[3 * node + m];
+        double g = g1 > g2 ? g1 : g2;
+        g = g < 0.0 ? 0.0 : g;
+        d2 = d2 + g * g;
+    }
+    const double nr = A.nr2[node];
+    const double r2 = sr2 > nr ? sr2 : nr;
+    return r2 < A.theta2 * d2;
+}
+
+// Kernel and its derivatives for one target (R = float or double pair terms).
+template <class R, bool GEN>
+__device__ __forceinline__ void term(const double (&xs)[3], const double (&ns)[3], const double* y,
+                                     const BhArgs& A, R& K, R (&dKdd)[3], R (&dKdN)[3])
+{
+    R d[3], n[3];
+    for (int m = 0; m < 3; ++m) {
+        d[m] = (R)(xs[m] - y[m]);
+        n[m] = (R)ns[m];
+    }
+    const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    const R q = n[0] * d[0] + n[1] * d[1] + n[2] * d[2];
+    const R inv = (R)1 / r2;
+    R Kqr;
+    if (!GEN) {
+        const R u = q * inv, u2 = u * u, u4 = u2 * u2;
+        K = u4 * u2;           // |q|^6 r2^-6
+        Kqr = u4 * u;          // sgn(q) |q|^5 r2^-5 = K r2 / q
+    } else {
+        const R aq = q < (R)0 ? -q : q;
+        if (aq == (R)0) {
+            K = (R)0;
+            Kqr = (R)0;
+        } else {
+            Kqr = (R)pow((double)aq, A.alpha - 1.0) * (R)pow((double)r2, 1.0 - 0.5 * A.beta);
+            Kqr = q < (R)0 ? -Kqr : Kqr;
+            K = Kqr * q * inv;
+        }
+    }
+    const R c1 = (R)A.alpha * Kqr * inv, c2 = (R)A.beta * K * inv;
+    for (int m = 0; m < 3; ++m) {
+        dKdd[m] = c1 * n[m] - c2 * d[m];
+        dKdN[m] = c1 * d[m];
+    }
+}
+
+template <class R, bool GEN, bool GRAD>
+__global__ __launch_bounds__(256) void k_bh_traverse(BhArgs A)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.nF) return;
+    const int32_t s = A.order[p];
+    const double4 X = A.dx[s], Nn = A.dn[s];
+    const double xs[3] = {X.x, X.y, X.z}, ns[3] = {Nn.x, Nn.y, Nn.z};
+    const double aS = X.w;
+    double slo[3], shi[3];
+    for (int m = 0; m < 3; ++m) {
+        slo[m] = A.flo[3 * s + m];
+        shi[m] = A.fhi[3 * s + m];
+    }
+    const double sr2 = A.fr2[s];
+    double gX[3] = {0, 0, 0}, gN[3] = {0, 0, 0}, ga = 0.0, e = 0.0;
+    unsigned long long nfar = 0, nnear = 0;
+
+    auto visit = [&](const double* y, double w, double* acc, int64_t stride) {
+        R K, dKdd[3], dKdN[3];
+        term<R, GEN>(xs, ns, y, A, K, dKdd, dKdN);
+        const double Kd = (double)K;
+        e += aS * w * Kd;
+        if (GRAD) {
+            const double f = aS * w;
+            for (int m = 0; m < 3; ++m) {
+                const double gd = f * (double)dKdd[m];
+                gX[m] += gd;
+                gN[m] += f * (double)dKdN[m];
+                unsafeAtomicAdd(acc + m * stride, -gd);
+            }
+            ga += w * Kd;
+            unsafeAtomicAdd(acc + 3 * stride, aS * Kd);
+        }
+    };
+
+    int64_t node = 1;
+    for (;;) {
+        bool down = false;
+        if (A.na[node] > 0.0) {
+            if (admissible(A, slo, shi, sr2, node)) {
+                visit(A.nX + 3 * node, A.na[node], A.accN + node, 2 * A.P);
+                ++nfar;
+            } else if (node >= A.P) {
+                const int64_t l = node - A.P;
+                const int64_t p1 = min((l + 1) * (int64_t)A.leaf, A.nF);
+                for (int64_t q = l * A.leaf; q < p1; ++q) {
+                    const int32_t t = A.order[q];
+                    if (t == s) continue;
+                    const double4 Y = A.dx[t];
+                    const double y[3] = {Y.x, Y.y, Y.z};
+                    visit(y, Y.w, A.accF + t, A.nF);
+                    ++nnear;
+                }
+            } else {
+                down = true;
+            }
+        }
+        if (down) {
+            node = 2 * node;
+            continue;
+        }
+        while (node & 1) node >>= 1;      // climb out of right children (and the root)
+        if (node == 0) break;
+        node += 1;                        // right sibling
+    }
+    A.eS[s] = e;
+    if (GRAD) {
+        for (int m = 0; m < 3; ++m) {
+            A.gS[m * A.nF + s] = gX[m];
+            A.gS[(3 + m) * A.nF + s] = gN[m];
+        }
+        A.gS[6 * A.nF + s] = ga;
+    }
+    atomicAdd(&A.counts[0], nfar);
+    atomicAdd(&A.counts[1], nnear);
+}
+
+// Per-face partial derivatives: face side + target side + the node terms of every
+// ancestor, written as gface[m * gstride + t] (dE/dX, dE/dN, dE/da).
+__global__ void k_bh_assemble(int64_t nF, int leaf, int64_t P, const int32_t* __restrict__ pos,
+                              const double4* __restrict__ dx, const double* __restrict__ na,
+                              const double* __restrict__ nX, const double* __restrict__ gS,
+                              const double* __restrict__ accF, const double* __restrict__ accN,
+                              double* __restrict__ gface, int64_t gstride)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nF) return;
+    const double4 X = dx[t];
+    const double xt[3] = {X.x, X.y, X.z};
+    double gx[3], ga = gS[6 * nF + t] + accF[3 * nF + t];
+    for (int m = 0; m < 3; ++m) gx[m] = gS[m * nF + t] + accF[m * nF + t];
+    const int64_t M = 2 * P;
+    for (int64_t node = P + pos[t] / leaf; node >= 1; node >>= 1) {
+        const double a = na[node];
+        if (!(a > 0.0)) continue;
+        double proj = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            const double g = accN[m * M + node];
+            gx[m] += (X.w / a) * g;
+            proj += (xt[m] - nX[3 * node + m]) * g;
+        }
+        ga += accN[3 * M + node] + proj / a;
+    }
+    for (int m = 0; m < 3; ++m) {
+        gface[m * gstride + t] = gx[m];
+        gface[(3 + m) * gstride + t] = gS[(3 + m) * nF + t];
+    }
+    gface[6 * gstride + t] = ga;
+}
+
+}  // namespace
+
+size_t bh_node_count(int64_t nF, int leaf, int64_t* P_out)
+{
+    const int64_t nleaf = (nF + leaf - 1) / leaf;
+    int64_t P = 1;
+    while (P < nleaf) P *= 2;
+    if (P_out) *P_out = P;
+    return (size_t)(2 * P);
+}
+
+size_t bh_sort_temp_bytes(int64_t nF)
+{
+    size_t bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                            (int)nF, 0, 62);
+    return bytes;
+}
+
+hipError_t launch_bh_build(const BhBuffers& b, const double* V, const int32_t* F, int64_t nF, int leaf,
+                           const FaceData& fd, hipStream_t s)
+{
+    int64_t P = 0;
+    const int64_t M = (int64_t)bh_node_count(nF, leaf, &P);
+    const unsigned g = (unsigned)((nF + 255) / 256);
+    hipLaunchKernelGGL(k_bh_faceprep, dim3(g), dim3(256), 0, s, V, F, nF, fd.dx, b.flo, b.fhi, b.fr2);
+    hipLaunchKernelGGL(k_bh_bbox, dim3(1), dim3(1024), 0, s, fd.dx, nF, b.box);
+    hipLaunchKernelGGL(k_bh_keys, dim3(g), dim3(256), 0, s, fd.dx, nF, b.box, b.keys_in);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    size_t tb = b.sort_bytes;
+    e = hipcub::DeviceRadixSort::SortKeys(b.sort_tmp, tb, b.keys_in, b.keys_out, (int)nF, 0, 62, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_bh_order, dim3(g), dim3(256), 0, s, b.keys_out, nF, b.order, b.pos);
+    hipLaunchKernelGGL(k_bh_leaves, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, nF, leaf, P, b.order,
+                       fd.dx, b.flo, b.fhi, b.na, b.nsx, b.nlo, b.nhi);
+    for (int64_t n0 = P / 2; n0 >= 1; n0 /= 2) {
+        const int64_t cnt = n0;   // nodes [n0, 2 n0)
+        hipLaunchKernelGGL(k_bh_level, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, n0, 2 * n0, b.na,
+                           b.nsx, b.nlo, b.nhi);
+    }
+    hipLaunchKernelGGL(k_bh_nodefinish, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, M, b.na, b.nsx,
+                       b.nlo, b.nhi, b.nX, b.nr2);
+    return hipGetLastError();
+}
+
+hipError_t launch_bh_eval(const BhBuffers& b, int64_t nF, int leaf, double theta, int precision, double alpha,
+                          double beta, const FaceData& fd, bool grad, double* gface, int64_t gstride,
+                          hipStream_t s)
+{
+    int64_t P = 0;
+    const int64_t M = (int64_t)bh_node_count(nF, leaf, &P);
+    hipError_t e = hipMemsetAsync(b.counts, 0, 2 * sizeof(unsigned long long), s);
+    if (e != hipSuccess) return e;
+    if (grad) {
+        if ((e = hipMemsetAsync(b.accF, 0, sizeof(double) * 4 * nF, s)) != hipSuccess) return e;
+        if ((e = hipMemsetAsync(b.accN, 0, sizeof(double) * 4 * M, s)) != hipSuccess) return e;
+    }
+    BhArgs A;
+    A.nF = nF; A.P = P; A.leaf = leaf; A.theta2 = theta * theta; A.alpha = alpha; A.beta = beta;
+    A.order = b.order; A.dx = fd.dx; A.dn = fd.dn; A.flo = b.flo; A.fhi = b.fhi; A.fr2 = b.fr2;
+    A.na = b.na; A.nX = b.nX; A.nlo = b.nlo; A.nhi = b.nhi; A.nr2 = b.nr2;
+    A.gS = b.gS; A.eS = b.eS; A.accF = b.accF; A.accN = b.accN; A.counts = b.counts;
+    const dim3 grid((unsigned)((nF + 255) / 256)), block(256);
+    const bool gen = !(alpha == 6.0 && beta == 12.0);
+    const bool f64 = precision == TP_PREC_FP64;
+#define TP_BH_LAUNCH(R, G, D) hipLaunchKernelGGL((k_bh_traverse<R, G, D>), grid, block, 0, s, A)
+    if (grad) {
+        if (f64) { if (gen) TP_BH_LAUNCH(double, true, true); else TP_BH_LAUNCH(double, false, true); }
+        else { if (gen) TP_BH_LAUNCH(float, true, true); else TP_BH_LAUNCH(float, false, true); }
+    } else {
+        if (f64) { if (gen) TP_BH_LAUNCH(double, true, false); else TP_BH_LAUNCH(double, false, false); }
+        else { if (gen) TP_BH_LAUNCH(float, true, false); else TP_BH_LAUNCH(float, false, false); }
+    }
+#undef TP_BH_LAUNCH
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (grad)
+        hipLaunchKernelGGL(k_bh_assemble, grid, block, 0, s, nF, leaf, P, b.pos, fd.dx, b.na, b.nX, b.gS, b.accF,
+                           b.accN, gface, gstride);
+    return hipGetLastError();
+}
+
+}  // namespace tp

@@ -249,6 +249,41 @@ size_t pcg_table_bytes(int n);
 hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, void* tab_host,
                             hipStream_t s);
 
+// Barnes-Hut approximation (tp_bh.hip).  Buffers are owned by the problem.
+struct BhBuffers {
+    double* flo = nullptr;        // [nF][3] face boxes
+    double* fhi = nullptr;
+    double* fr2 = nullptr;        // [nF]
+    double* box = nullptr;        // [6] barycenter bounding box
+    uint64_t* keys_in = nullptr;  // [nF]
+    uint64_t* keys_out = nullptr; // [nF]
+    void* sort_tmp = nullptr;
+    size_t sort_bytes = 0;
+    int32_t* order = nullptr;     // [nF] sorted position -> face
+    int32_t* pos = nullptr;       // [nF] face -> sorted position
+    double* na = nullptr;         // [M]  (M = 2P nodes, heap order)
+    double* nsx = nullptr;        // [M][3]
+    double* nX = nullptr;         // [M][3]
+    double* nlo = nullptr;        // [M][3]
+    double* nhi = nullptr;        // [M][3]
+    double* nr2 = nullptr;        // [M]
+    double* gS = nullptr;         // [7][nF]
+    double* eS = nullptr;         // [nF]
+    double* accF = nullptr;       // [4][nF]
+    double* accN = nullptr;       // [4][M]
+    unsigned long long* counts = nullptr;   // [2] far, near terms
+};
+size_t bh_node_count(int64_t nF, int leaf, int64_t* P_out);
+size_t bh_sort_temp_bytes(int64_t nF);
+// Tree of the faces described by fd, whose vertices are V.
+hipError_t launch_bh_build(const BhBuffers& b, const double* V, const int32_t* F, int64_t nF, int leaf,
+                           const FaceData& fd, hipStream_t s);
+// E_BH rows into b.eS and, with grad, the per-face partial derivatives into gface
+// ([7][gstride]: dE/dX, dE/dN, dE/da).
+hipError_t launch_bh_eval(const BhBuffers& b, int64_t nF, int leaf, double theta, int precision, double alpha,
+                          double beta, const FaceData& fd, bool grad, double* gface, int64_t gstride,
+                          hipStream_t s);
+
 // ------------------------------------------------------------------ device-side sync
 
 constexpr unsigned long long kSpinLimit = 1ull << 22;

@@ -36,7 +36,7 @@ EXPORTED = [
     "tp_problem_fractional_apply", "tp_problem_precond_apply", "tp_step_opts_default",
     "tp_precond_step", "tp_last_error", "tp_profile_enable", "tp_profile_reset", "tp_profile_get",
     "tp_problem_poisson_solve", "tp_batch_step", "tp_problem_device_bytes",
-    "tp_estimate_device_bytes",
+    "tp_estimate_device_bytes", "tp_problem_bh_stats",
 ]
 
 
@@ -49,7 +49,7 @@ class TpError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("precision", ctypes.c_int), ("cg_rtol", ctypes.c_double), ("cg_maxiter", ctypes.c_int),
-                ("cg_precond", ctypes.c_int)]
+                ("cg_precond", ctypes.c_int), ("theta", ctypes.c_double), ("leaf_size", ctypes.c_int)]
 
 
 class SolveReport(ctypes.Structure):
@@ -117,6 +117,7 @@ def lib() -> ctypes.CDLL:
         "tp_precond_step": [vp, P(StepOpts), P(StepReport), vp],
         "tp_batch_step": [P(vp), i32, P(StepOpts), P(StepReport), P(i32)],
         "tp_problem_device_bytes": [vp, P(ctypes.c_uint64)],
+        "tp_problem_bh_stats": [vp, P(i64), P(i64)],
         "tp_estimate_device_bytes": [i64, i64, i32, i32, P(Params), i32, P(ctypes.c_uint64)],
         "tp_profile_enable": [i32],
         "tp_profile_reset": [],
@@ -321,6 +322,12 @@ class Problem:
         ptr = direction.data_ptr() if direction is not None else None
         _check(lib().tp_precond_step(self._h, ctypes.byref(opts or step_opts()), ctypes.byref(rep), ptr))
         return rep
+
+    def bh_stats(self):
+        """(far, near) term counts of the last Barnes-Hut evaluation."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tp_problem_bh_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return int(a.value), int(b.value)
 
     def device_bytes(self) -> int:
         b = ctypes.c_uint64()
