@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", type=int, default=0, help="0 fp32 hi/lo, 1 fp32, 2 fp64")
+    ap.add_argument("--precision", type=int, default=3,
+                    help="0 fp32 hi/lo, 1 fp32, 2 fp64, 3 fp32 hi/lo + fp64 near field (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serve-requests", type=int, default=48,
@@ -51,6 +52,8 @@ def parse():
     ap.add_argument("--serve-steps", type=int, default=4)
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving comparison and print its JSON line")
+    ap.add_argument("--sweep", action="store_true",
+                    help="precision and Barnes-Hut sweep (bumpy sphere, linked tori) instead of the step")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 256 MiB device copy 5 times (counter calibration)")
     return ap.parse_args()
@@ -113,6 +116,67 @@ def cpu_baseline(mesh, u, target_s: float):
                    f"extrapolated over all {nF} rows, 2 fractional applies, 2 solves = {t_step:.1f} s"),
         "est_step_s": t_step,
     }
+
+
+def _timed(fn, reps=3):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    best = float("inf")
+    out = None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    return out, best * 1e3
+
+
+def sweep():
+    """E and dE of the 327,680-face bumpy sphere (icosphere level 7, harmonic bumps l <= 8,
+    amplitude 0.05) in every variant against the FP64 direct sums on the GPU (which the GPU
+    tests hold to the oracle at sampled vertices of the same mesh), and direct vs
+    Barnes-Hut on the linked tori (51,200 faces).  Times are wall time of one synchronous
+    E + dE call (best of 3)."""
+    import numpy as np
+    import torch
+    from paper_2107_01664_amd import meshgen as mg
+    from paper_2107_01664_amd import tpsurf as tp
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+    report = {}
+    for wname in ("bumpy327k", "linked_tori"):
+        m = mg.workload(wname)
+        V = torch.from_numpy(m.V).cuda()
+        F = torch.from_numpy(m.F).cuda()
+        rows = {}
+        ref = None
+        variants = [("fp64 direct", dict(precision=2)), ("fp32 direct, fp64 accumulation", dict(precision=1)),
+                    ("fp32 hi/lo direct, fp64 accumulation", dict(precision=0)),
+                    ("fp32 hi/lo direct + fp64 near field (default)", dict(precision=3)),
+                    ("barnes-hut theta=0.5 fp32", dict(precision=0, theta=0.5)),
+                    ("barnes-hut theta=0.25 fp32", dict(precision=0, theta=0.25)),
+                    ("barnes-hut theta=0.5 fp64", dict(precision=2, theta=0.5))]
+        for name, kw in variants:
+            with tp.Problem(V, F, tp.default_params(**kw)) as P:
+                (E, g), ms = _timed(lambda: P.gradient())
+                g = g.cpu().numpy()
+                terms = P.bh_stats() if kw.get("theta") else None
+            if ref is None:
+                ref = (E, g)
+                rows[name] = {"E": E, "ms": ms}
+                print(f"[sweep] {wname} {name}: {ms:.1f} ms", file=sys.stderr, flush=True)
+                continue
+            r = {"E": E, "ms": ms, "E_rel_err": abs(E - ref[0]) / ref[0], "dE_rel_err": rel(g, ref[1])}
+            if terms:
+                r["terms_far_near"] = list(terms)
+            rows[name] = r
+            print(f"[sweep] {wname} {name}: {ms:.1f} ms, E {r['E_rel_err']:.2e}, dE {r['dE_rel_err']:.2e}",
+                  file=sys.stderr, flush=True)
+        report[wname] = {"faces": m.nF, "pairs": float(m.nF) * (m.nF - 1), "variants": rows}
+    return report
 
 
 def _build(spec):
@@ -212,6 +276,9 @@ def main():
     if a.copy_probe:
         copy_probe()
         return
+    if a.sweep:
+        print(json.dumps(sweep()), flush=True)
+        return
     tp.lib()
     if a.serve_only:
         print(json.dumps(serving_bench(*serve_mesh, a.serve_steps, a.serve_fmax, verbose=True)), flush=True)
@@ -273,7 +340,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {0: "fp32", 1: "fp32", 2: "f64"}[a.precision],
+        "dtype": {0: "fp32", 1: "fp32", 2: "f64", 3: "fp32"}[a.precision],
         "data": "synthetic",
         "config": {
             "workload": ("torus40k: torus R=1 r=0.3 on a 200x100 grid (40,000 faces), vertex noise "
@@ -284,7 +351,9 @@ def main():
             "alpha": 6, "beta": 12, "sigma": 1.0 / 3.0,
             "precision": {0: "fp32 pair terms, hi/lo barycenters, fp64 accumulation",
                           1: "fp32 pair terms, fp64 accumulation",
-                          2: "fp64 pair terms"}[a.precision],
+                          2: "fp64 pair terms",
+                          3: "fp32 pair terms, hi/lo barycenters, fp64 accumulation; pairs closer "
+                             "than 2 mean edge lengths in fp64"}[a.precision],
             "pairs_per_step": pairs_per_step,
             "parallelism": "single GPU",
         },

@@ -66,7 +66,12 @@ typedef enum {
     TP_PREC_FP32_HILO = 0,  /* FP32 pair terms; barycenter differences from hi+lo FP32
                                splits of the FP64 barycenters (default)                   */
     TP_PREC_FP32 = 1,       /* FP32 pair terms from FP32-rounded barycenters              */
-    TP_PREC_FP64 = 2        /* FP64 pair terms                                            */
+    TP_PREC_FP64 = 2,       /* FP64 pair terms                                            */
+    TP_PREC_FP32_NEAR64 = 3 /* as TP_PREC_FP32_HILO for the energy and its differential,
+                               except that pairs whose barycenters are closer than twice
+                               the mean edge length of the problem's first mesh (tested on
+                               the FP32 hi+lo distance) are summed in FP64; the fractional
+                               apply is as TP_PREC_FP32_HILO                               */
 } tp_precision;
 
 typedef struct {

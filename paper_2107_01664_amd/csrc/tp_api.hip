@@ -256,6 +256,7 @@ struct tp_problem {
     DevBuf<unsigned long long> bh_counts;
     BhBuffers bh;
     const double* fd_V = nullptr;    // vertices the face data currently describe
+    double rho2 = 0.0;               // FP64 near-field radius^2: (2 x mean edge of the first mesh)^2
 
     // pinned host mirrors of device scalars, flags and CG results; multi-problem CG tables
     HostBuf<double> hs, hrelres;
@@ -314,7 +315,7 @@ tp_status validate_params(const tp_params* in, tp_params& out, double& sigma)
         return fail(TP_E_INVALID_ARGUMENT, "alpha must be a finite number > 1");
     if (!(out.beta > 0.0) || !std::isfinite(out.beta))
         return fail(TP_E_INVALID_ARGUMENT, "beta must be a finite number > 0");
-    if (out.precision < 0 || out.precision > 2) return fail(TP_E_INVALID_ARGUMENT, "unknown precision");
+    if (out.precision < 0 || out.precision > 3) return fail(TP_E_INVALID_ARGUMENT, "unknown precision");
     if (!(out.cg_rtol > 0.0)) return fail(TP_E_INVALID_ARGUMENT, "cg_rtol must be > 0");
     if (out.cg_maxiter < 1) return fail(TP_E_INVALID_ARGUMENT, "cg_maxiter must be >= 1");
     if (out.cg_precond != 0 && out.cg_precond != 1) return fail(TP_E_INVALID_ARGUMENT, "cg_precond must be 0 or 1");
@@ -760,6 +761,25 @@ double gradient_energy(const tp_problem* P, double v)
 
 // ------------------------------------------------------------------ all-pairs phases
 
+bool near_field(const tp_problem* P) { return P->prm.precision == TP_PREC_FP32_NEAR64; }
+
+// The FP64 near-field slice (index `slice` of the partial buffer, nacc accumulators) of
+// every problem of the batch that uses it.
+tp_status enqueue_near(const Batch& B, const std::vector<PairPlan>& plans, int nacc, bool grad)
+{
+    for (size_t m = 0; m < B.size(); ++m) {
+        tp_problem* P = B[m];
+        if (!near_field(P)) continue;
+        const PairPlan& pl = plans[m];
+        TP_TRY(ensure_bh(P));
+        TP_HIP(launch_bh_build(P->bh, P->fd_V, P->F.p, P->nF, P->prm.leaf_size, P->fd, P->stream));
+        double* slice = P->part.p + (size_t)pl.n_split * nacc * pl.irows;
+        TP_HIP(launch_near64(P->bh, P->nF, P->prm.leaf_size, P->rho2, P->fd, P->prm.alpha, P->prm.beta, grad, slice,
+                             pl.irows, P->stream));
+    }
+    return TP_OK;
+}
+
 // E of every problem (face data must describe the point of evaluation) -> scal[slot].
 tp_status enqueue_energy(const Batch& B, int slot)
 {
@@ -775,9 +795,11 @@ tp_status enqueue_energy(const Batch& B, int slot)
     double pairs = 0;
     for (tp_problem* P : B) {
         const PairPlan pl = plan_for(kKindEnergy, prec, 1, P->nF, P->cap);
-        TP_TRY(P->part.ensure((size_t)pl.n_split * pl.irows, s));
+        const int slices = pl.n_split + (near_field(P) ? 1 : 0);
+        TP_TRY(P->part.ensure((size_t)slices * pl.irows, s));
         TP_TRY(P->gface.ensure((size_t)pl.irows, s));
         jobs.push_back(make_pair_job(P->fd, pl, P->part.p));
+        jobs.back().rho2 = (float)P->rho2;
         plans.push_back(pl);
         pairs += (double)P->nF * (double)(P->nF - 1);
     }
@@ -786,10 +808,12 @@ tp_status enqueue_energy(const Batch& B, int slot)
         TP_HIP(launch_pairs_energy(jobs.data(), (int)jobs.size(), prec, B[0]->prm.alpha, B[0]->prm.beta, s));
         t.stop();
     }
+    TP_TRY(enqueue_near(B, plans, 1, false));
     for (size_t m = 0; m < B.size(); ++m) {
         tp_problem* P = B[m];
         const PairPlan& pl = plans[m];
-        TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, 1, pl.irows, P->nF, P->gface.p, pl.irows, s));
+        const int slices = pl.n_split + (near_field(P) ? 1 : 0);
+        TP_HIP(launch_reduce_splits(P->part.p, slices, 1, pl.irows, P->nF, P->gface.p, pl.irows, s));
         // E = sum_S a_S sum_T a_T K(S,T)
         TP_HIP(launch_dot_cols(&P->dx.p[0].w, 4, P->gface.p, 1, P->nF, 1, P->red.p, P->scal.p + slot, s));
     }
@@ -812,9 +836,11 @@ tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
     for (tp_problem* P : B) {
         TP_TRY(ensure_vf(P));
         const PairPlan pl = plan_for(kKindGrad, prec, 1, P->nF, P->cap);
-        TP_TRY(P->part.ensure((size_t)pl.n_split * 7 * pl.irows, s));
+        const int slices = pl.n_split + (near_field(P) ? 1 : 0);
+        TP_TRY(P->part.ensure((size_t)slices * 7 * pl.irows, s));
         TP_TRY(P->gface.ensure((size_t)7 * pl.irows, s));
         jobs.push_back(make_pair_job(P->fd, pl, P->part.p));
+        jobs.back().rho2 = (float)P->rho2;
         plans.push_back(pl);
         pairs += (double)P->nF * (double)(P->nF - 1);
     }
@@ -823,10 +849,12 @@ tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
         TP_HIP(launch_pairs_grad(jobs.data(), (int)jobs.size(), prec, B[0]->prm.alpha, B[0]->prm.beta, s));
         t.stop();
     }
+    TP_TRY(enqueue_near(B, plans, 7, true));
     for (size_t m = 0; m < B.size(); ++m) {
         tp_problem* P = B[m];
         const PairPlan& pl = plans[m];
-        TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, 7, pl.irows, P->nF, P->gface.p, pl.irows, s));
+        const int slices = pl.n_split + (near_field(P) ? 1 : 0);
+        TP_HIP(launch_reduce_splits(P->part.p, slices, 7, pl.irows, P->nF, P->gface.p, pl.irows, s));
         TP_HIP(launch_grad_gather(P->V.p, P->F.p, P->nV, P->nF, P->vf_off.p, P->vf_idx.p, P->gface.p,
                                   pl.irows, dE[m], s));
         // 2E = sum_S a_S dE/da_S, since dE/da_S = sum_T a_T (K(S,T) + K(T,S))
@@ -1167,6 +1195,16 @@ tp_status create_problem(const double* V, int64_t nV, const int32_t* F, int64_t 
         return bail(fail(TP_E_DEVICE, "index check launch failed"));
     if ((st = check_flags(P)) != TP_OK) return bail(st);
     if ((st = geometry(P)) != TP_OK) return bail(st);
+    if (P->prm.precision == TP_PREC_FP32_NEAR64) {
+        if ((st = P->edge.ensure(P->nF, stream)) != TP_OK) return bail(st);
+        hipLaunchKernelGGL(k_face_edges, dim3((unsigned)((nF + 255) / 256)), dim3(256), 0, stream, P->V.p, P->F.p,
+                           nF, P->edge.p);
+        double es = 0;
+        if (hipGetLastError() != hipSuccess) return bail(fail(TP_E_DEVICE, "edge length launch failed"));
+        if ((st = device_sum(P, P->edge.p, 1, nF, &es)) != TP_OK) return bail(st);
+        const double h = es / (3.0 * (double)nF);
+        P->rho2 = 4.0 * h * h;
+    }
     *out = P;
     return TP_OK;
 }
@@ -1593,7 +1631,7 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
     const PairPlan pg = plan_for(kKindGrad, prec, 1, nF, cap);
     const int kf = std::min(ncol, kMaxGroupCols);
     const PairPlan pf = plan_for(kKindFrac, prec, kf, nF, cap);
-    const double part = std::max({(double)pe.n_split * pe.irows, 7.0 * pg.n_split * pg.irows,
+    const double part = std::max({(double)(pe.n_split + 1) * pe.irows, 7.0 * (pg.n_split + 1) * pg.irows,
                                   (double)kf * pf.n_split * pf.irows});
     const double gface = std::max((double)pe.irows, 7.0 * pg.irows);
     const double esz = prec == TP_PREC_FP64 ? 8 : 4;
@@ -1601,7 +1639,7 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
     // step work arrays, per-face volumes and edge lengths, CG tables
     b += 8 * n * ncol * 4 + 8 * n * 3 * 3 + 16 * f + 4096;
     // Barnes-Hut tree, keys, sort scratch and per-face sums
-    if (prm.theta > 0.0) {
+    if (prm.theta > 0.0 || prm.precision == TP_PREC_FP32_NEAR64) {
         const double M = (double)bh_node_count(nF, prm.leaf_size, nullptr);
         b += f * (176.0 + 56.0) + M * 144.0 + (double)bh_sort_temp_bytes(nF) + 64;
     }
@@ -1635,7 +1673,7 @@ tp_status tp_params_default(tp_params* p)
     p->alpha = 6.0;
     p->beta = 12.0;
     p->sigma = -1.0;
-    p->precision = TP_PREC_FP32_HILO;
+    p->precision = TP_PREC_FP32_NEAR64;
     p->cg_rtol = 1e-10;
     p->cg_maxiter = 20000;
     p->cg_precond = 1;
@@ -1829,6 +1867,8 @@ tp_status tp_energy_faces(const double* X, const double* N, const double* a, int
     TP_TRY(validate_params(params, P->prm, P->sigma));
     if (P->prm.theta > 0.0)
         return fail(TP_E_INVALID_ARGUMENT, "Barnes-Hut (theta > 0) needs the mesh: use tp_energy or a problem");
+    if (P->prm.precision == TP_PREC_FP32_NEAR64)
+        return fail(TP_E_INVALID_ARGUMENT, "TP_PREC_FP32_NEAR64 needs the mesh: use tp_energy or a problem");
     (void)hipGetDevice(&P->device);
     P->stream = (hipStream_t)stream;
     P->nF = nF;

@@ -390,7 +390,167 @@ __global__ void k_bh_assemble(int64_t nF, int leaf, int64_t P, const int32_t* __
     gface[6 * gstride + t] = ga;
 }
 
+// ------------------------------------------------------------------ FP64 near field
+
+struct NearArgs {
+    int64_t nF, P;
+    int leaf;
+    double prune2;        // subtrees farther than this (squared, from X_S) hold no near pair
+    float rho2;           // a pair is near when its FP32 hi+lo squared distance is < rho2
+    double alpha, beta;
+    const int32_t* order;
+    const float4* fx;
+    const float4* fl;
+    const double4* dx;
+    const double4* dn;
+    const double* na;
+    const double* nlo;
+    const double* nhi;
+    double* out;
+    int64_t irows;
+};
+
+// FP64 kernel of one ordered pair: K and K r2 / q (0 for q = 0).
+template <bool GEN>
+__device__ __forceinline__ void kg64(double q, double r2, double inv, double alpha, double beta, double& K,
+                                     double& Kqr)
+{
+    if (!GEN) {
+        const double u = q * inv, u2 = u * u, u4 = u2 * u2;
+        K = u4 * u2;
+        Kqr = u4 * u;
+    } else {
+        if (q == 0.0) {
+            K = 0.0;
+            Kqr = 0.0;
+            return;
+        }
+        Kqr = copysign(pow(fabs(q), alpha - 1.0) * pow(r2, 1.0 - 0.5 * beta), q);
+        K = Kqr * q * inv;
+    }
+}
+
+// One thread per face (Morton order): the pairs (S, T) that the FP32 kernels leave out,
+// in FP64, with the same per-face accumulators and epilogue as the all-pairs kernels.
+template <bool GEN, bool GRAD>
+__global__ __launch_bounds__(256) void k_near64(NearArgs A)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.nF) return;
+    const int32_t s = A.order[p];
+    const float4 sh = A.fx[s], sl = A.fl[s];
+    const double4 X = A.dx[s], Nn = A.dn[s];
+    double c[11];
+    for (int m = 0; m < 11; ++m) c[m] = 0.0;
+    double e = 0.0;
+    int64_t node = 1;
+    for (;;) {
+        bool down = false;
+        if (A.na[node] > 0.0) {
+            double d2 = 0.0;
+            const double xs[3] = {X.x, X.y, X.z};
+            for (int m = 0; m < 3; ++m) {
+                const double g1 = A.nlo[3 * node + m] - xs[m], g2 = xs[m] - A.nhi[3 * node + m];
+                double g = g1 > g2 ? g1 : g2;
+                g = g < 0.0 ? 0.0 : g;
+                d2 += g * g;
+            }
+            if (d2 <= A.prune2) {
+                if (node >= A.P) {
+                    const int64_t l = node - A.P;
+                    const int64_t q1 = min((l + 1) * (int64_t)A.leaf, A.nF);
+                    for (int64_t qq = l * A.leaf; qq < q1; ++qq) {
+                        const int32_t t = A.order[qq];
+                        if (t == s) continue;
+                        const float4 th = A.fx[t], tl = A.fl[t];
+                        const float fdx = (sh.x - th.x) + (sl.x - tl.x);
+                        const float fdy = (sh.y - th.y) + (sl.y - tl.y);
+                        const float fdz = (sh.z - th.z) + (sl.z - tl.z);
+                        const float r2f = __builtin_fmaf(fdz, fdz, __builtin_fmaf(fdy, fdy, fdx * fdx));
+                        if (!(r2f < A.rho2)) continue;
+                        const double4 Y = A.dx[t], Nt = A.dn[t];
+                        const double dx = X.x - Y.x, dy = X.y - Y.y, dz = X.z - Y.z;
+                        const double r2 = dx * dx + dy * dy + dz * dz;
+                        const double inv = 1.0 / r2;
+                        const double q = Nn.x * dx + Nn.y * dy + Nn.z * dz;
+                        double K, Kqr;
+                        kg64<GEN>(q, r2, inv, A.alpha, A.beta, K, Kqr);
+                        if (!GRAD) {
+                            e += K * Y.w;
+                            continue;
+                        }
+                        const double qp = Nt.x * dx + Nt.y * dy + Nt.z * dz;
+                        double Kp, Kpqr;
+                        kg64<GEN>(qp, r2, inv, A.alpha, A.beta, Kp, Kpqr);
+                        const double tt = Y.w * inv;
+                        const double aq = Kqr * tt, ap = Kpqr * tt, KK = K + Kp, cc = KK * tt;
+                        c[0] += aq;
+                        c[1] += ap * Nt.x;
+                        c[2] += ap * Nt.y;
+                        c[3] += ap * Nt.z;
+                        c[4] += cc * dx;
+                        c[5] += cc * dy;
+                        c[6] += cc * dz;
+                        c[7] += aq * dx;
+                        c[8] += aq * dy;
+                        c[9] += aq * dz;
+                        c[10] += KK * Y.w;
+                    }
+                } else {
+                    down = true;
+                }
+            }
+        }
+        if (down) {
+            node = 2 * node;
+            continue;
+        }
+        while (node & 1) node >>= 1;
+        if (node == 0) break;
+        node += 1;
+    }
+    if (!GRAD) {
+        A.out[s] = e;
+        return;
+    }
+    const double aS = X.w, al = A.alpha, be = A.beta;
+    double o[7];
+    o[0] = aS * (al * (Nn.x * c[0] + c[1]) - be * c[4]);
+    o[1] = aS * (al * (Nn.y * c[0] + c[2]) - be * c[5]);
+    o[2] = aS * (al * (Nn.z * c[0] + c[3]) - be * c[6]);
+    o[3] = aS * al * c[7];
+    o[4] = aS * al * c[8];
+    o[5] = aS * al * c[9];
+    o[6] = c[10];
+    for (int m = 0; m < 7; ++m) A.out[m * A.irows + s] = o[m];
+}
+
 }  // namespace
+
+hipError_t launch_near64(const BhBuffers& b, int64_t nF, int leaf, double rho2, const FaceData& fd,
+                         double alpha, double beta, bool grad, double* out, int64_t irows, hipStream_t s)
+{
+    int64_t P = 0;
+    (void)bh_node_count(nF, leaf, &P);
+    NearArgs A;
+    A.nF = nF; A.P = P; A.leaf = leaf;
+    A.prune2 = rho2 * 1.001 + 1e-300;      // the FP32 distance may be short of the exact one
+    A.rho2 = (float)rho2;
+    A.alpha = alpha; A.beta = beta;
+    A.order = b.order; A.fx = fd.fx; A.fl = fd.fl; A.dx = fd.dx; A.dn = fd.dn;
+    A.na = b.na; A.nlo = b.nlo; A.nhi = b.nhi;
+    A.out = out; A.irows = irows;
+    const dim3 grid((unsigned)((nF + 255) / 256)), block(256);
+    const bool gen = !(alpha == 6.0 && beta == 12.0);
+    if (grad) {
+        if (gen) hipLaunchKernelGGL((k_near64<true, true>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_near64<false, true>), grid, block, 0, s, A);
+    } else {
+        if (gen) hipLaunchKernelGGL((k_near64<true, false>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_near64<false, false>), grid, block, 0, s, A);
+    }
+    return hipGetLastError();
+}
 
 size_t bh_node_count(int64_t nF, int leaf, int64_t* P_out)
 {

@@ -103,6 +103,7 @@ struct PairJob {
     double* part = nullptr;         // partial buffer [n_split][nacc][irows]
     int64_t irows = 0;
     int n_itiles = 0, tiles_per_split = 0, ntiles_j = 0, block0 = 0;
+    float rho2 = 0.f;               // TP_PREC_FP32_NEAR64: pairs with r2 < rho2 are left out
 };
 constexpr int kMaxPairJobs = 16;
 PairJob make_pair_job(const FaceData& fd, const PairPlan& pl, double* part, const void* ub = nullptr);
@@ -283,6 +284,14 @@ hipError_t launch_bh_build(const BhBuffers& b, const double* V, const int32_t* F
 hipError_t launch_bh_eval(const BhBuffers& b, int64_t nF, int leaf, double theta, int precision, double alpha,
                           double beta, const FaceData& fd, bool grad, double* gface, int64_t gstride,
                           hipStream_t s);
+
+// FP64 near field (TP_PREC_FP32_NEAR64): for every face S, the pairs (S, T), T != S, whose
+// FP32 hi+lo barycenter distance satisfies r2 < rho2 (the pairs the FP32 kernels leave
+// out), found with the Barnes-Hut tree of the current face data, summed in FP64.  With
+// grad, out is one [7][irows] slice of the gradient partials; else one [irows] slice of
+// the energy partials.
+hipError_t launch_near64(const BhBuffers& b, int64_t nF, int leaf, double rho2, const FaceData& fd,
+                         double alpha, double beta, bool grad, double* out, int64_t irows, hipStream_t s);
 
 // ------------------------------------------------------------------ device-side sync
 

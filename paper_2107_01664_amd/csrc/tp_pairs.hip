@@ -80,7 +80,11 @@ struct PowGen {
     }
     __device__ __forceinline__ void KG(float q, float r2, float inv, float& K, float& Kqr) const
     {
-        (void)inv;
+        if (r2 == INFINITY) {      // a pair left out of the FP32 sums
+            K = 0.0f;
+            Kqr = 0.0f;
+            return;
+        }
         float e = am1 * log2_fast(fabsf(q)) + (1.0f - hb) * log2_fast(r2);
         Kqr = copysignf(exp2_fast(e), q);
         K = Kqr * q * inv;
@@ -140,11 +144,18 @@ __device__ __forceinline__ bool tile_hits_diag(int64_t j0, int64_t ibase, int is
 
 // ============================================================== energy (FP32)
 
-template <bool DIAG, int NI, bool HILO, class Pow>
+// Squared FP32 distance of a pair, in one fixed sequence of operations (the FP64 near
+// field repeats it bit for bit to decide which pairs it owns).
+__device__ __forceinline__ float dist2_32(float dx, float dy, float dz)
+{
+    return __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
+}
+
+template <bool DIAG, int NI, bool HILO, bool NEAR, class Pow>
 __device__ __forceinline__ void energy_tile32(const float4* s_x, const float4* s_l, int64_t j0,
                                               const float3 (&Sh)[NI], const float3 (&Sl)[NI],
                                               const float3 (&Sn)[NI], const int64_t (&Si)[NI],
-                                              const Pow& pw, float (&c)[NI])
+                                              const Pow& pw, float rho2, float (&c)[NI])
 {
 #pragma unroll 4
     for (int jj = 0; jj < kTileJ; ++jj) {
@@ -163,8 +174,9 @@ __device__ __forceinline__ void energy_tile32(const float4* s_x, const float4* s
                 dy = Sh[r].y - tx.y;
                 dz = Sh[r].z - tx.z;
             }
-            float r2 = dx * dx + dy * dy + dz * dz;
+            float r2 = dist2_32(dx, dy, dz);
             if (DIAG) r2 = (Si[r] == j0 + jj) ? 1.0f : r2;
+            if (NEAR) r2 = r2 < rho2 ? INFINITY : r2;   // summed by the FP64 near field
             const float inv = rcp_fast(r2);
             const float q = Sn[r].x * dx + Sn[r].y * dy + Sn[r].z * dz;
             c[r] += pw.K(q, r2, inv) * tx.w;
@@ -172,7 +184,7 @@ __device__ __forceinline__ void energy_tile32(const float4* s_x, const float4* s
     }
 }
 
-template <int NI, bool HILO, class Pow>
+template <int NI, bool HILO, bool NEAR, class Pow>
 __global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
 {
     const PairJob J = pick_job(jb);
@@ -214,9 +226,9 @@ __global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
 #pragma unroll
         for (int r = 0; r < NI; ++r) c[r] = 0.f;
         if (tile_hits_diag(j0, ibase, kBlock * NI))
-            energy_tile32<true, NI, HILO>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, c);
+            energy_tile32<true, NI, HILO, NEAR>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
         else
-            energy_tile32<false, NI, HILO>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, c);
+            energy_tile32<false, NI, HILO, NEAR>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
 #pragma unroll
         for (int r = 0; r < NI; ++r) acc[r] += (double)c[r];
     }
@@ -238,11 +250,11 @@ __global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
 constexpr int kGradAcc = 11;
 constexpr int kGradOut = 7;     // dE/dX (3), dE/dN (3), dE/da (1)
 
-template <bool DIAG, int NI, bool HILO, class Pow>
+template <bool DIAG, int NI, bool HILO, bool NEAR, class Pow>
 __device__ __forceinline__ void grad_tile32(const float4* s_x, const float4* s_l, const float4* s_n,
                                             int64_t j0, const float3 (&Sh)[NI],
                                             const float3 (&Sl)[NI], const float3 (&Sn)[NI],
-                                            const int64_t (&Si)[NI], const Pow& pw,
+                                            const int64_t (&Si)[NI], const Pow& pw, float rho2,
                                             float (&c)[NI][kGradAcc])
 {
 #pragma unroll 2
@@ -264,8 +276,9 @@ __device__ __forceinline__ void grad_tile32(const float4* s_x, const float4* s_l
                 dy = Sh[r].y - tx.y;
                 dz = Sh[r].z - tx.z;
             }
-            float r2 = dx * dx + dy * dy + dz * dz;
+            float r2 = dist2_32(dx, dy, dz);
             if (DIAG) r2 = (Si[r] == j0 + jj) ? 1.0f : r2;
+            if (NEAR) r2 = r2 < rho2 ? INFINITY : r2;   // summed by the FP64 near field
             const float inv = rcp_fast(r2);
             const float q = Sn[r].x * dx + Sn[r].y * dy + Sn[r].z * dz;
             const float qp = tn.x * dx + tn.y * dy + tn.z * dz;
@@ -292,7 +305,7 @@ __device__ __forceinline__ void grad_tile32(const float4* s_x, const float4* s_l
     }
 }
 
-template <int NI, bool HILO, class Pow>
+template <int NI, bool HILO, bool NEAR, class Pow>
 __global__ __launch_bounds__(kBlock) void k_grad32(PairBatch jb, double alpha, double beta, Pow pw)
 {
     const PairJob J = pick_job(jb);
@@ -339,9 +352,9 @@ __global__ __launch_bounds__(kBlock) void k_grad32(PairBatch jb, double alpha, d
 #pragma unroll
             for (int m = 0; m < kGradAcc; ++m) c[r][m] = 0.f;
         if (tile_hits_diag(j0, ibase, kBlock * NI))
-            grad_tile32<true, NI, HILO>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, c);
+            grad_tile32<true, NI, HILO, NEAR>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
         else
-            grad_tile32<false, NI, HILO>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, c);
+            grad_tile32<false, NI, HILO, NEAR>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
 #pragma unroll
         for (int r = 0; r < NI; ++r)
 #pragma unroll
@@ -769,29 +782,36 @@ const void* energy_fn(int precision, bool p6)
 {
     if (precision == TP_PREC_FP64)
         return p6 ? (const void*)k_energy64<PowP6> : (const void*)k_energy64<PowGen>;
+    if (precision == TP_PREC_FP32_NEAR64)
+        return p6 ? (const void*)k_energy32<kNiEnergy32, true, true, PowP6>
+                  : (const void*)k_energy32<kNiEnergy32, true, true, PowGen>;
     const bool hilo = precision == TP_PREC_FP32_HILO;
-    if (p6) return hilo ? (const void*)k_energy32<kNiEnergy32, true, PowP6>
-                        : (const void*)k_energy32<kNiEnergy32, false, PowP6>;
-    return hilo ? (const void*)k_energy32<kNiEnergy32, true, PowGen>
-                : (const void*)k_energy32<kNiEnergy32, false, PowGen>;
+    if (p6) return hilo ? (const void*)k_energy32<kNiEnergy32, true, false, PowP6>
+                        : (const void*)k_energy32<kNiEnergy32, false, false, PowP6>;
+    return hilo ? (const void*)k_energy32<kNiEnergy32, true, false, PowGen>
+                : (const void*)k_energy32<kNiEnergy32, false, false, PowGen>;
 }
 
 const void* grad_fn(int precision, bool p6)
 {
     if (precision == TP_PREC_FP64)
         return p6 ? (const void*)k_grad64<PowP6> : (const void*)k_grad64<PowGen>;
+    if (precision == TP_PREC_FP32_NEAR64)
+        return p6 ? (const void*)k_grad32<kNiGrad32, true, true, PowP6>
+                  : (const void*)k_grad32<kNiGrad32, true, true, PowGen>;
     const bool hilo = precision == TP_PREC_FP32_HILO;
-    if (p6) return hilo ? (const void*)k_grad32<kNiGrad32, true, PowP6>
-                        : (const void*)k_grad32<kNiGrad32, false, PowP6>;
-    return hilo ? (const void*)k_grad32<kNiGrad32, true, PowGen>
-                : (const void*)k_grad32<kNiGrad32, false, PowGen>;
+    if (p6) return hilo ? (const void*)k_grad32<kNiGrad32, true, false, PowP6>
+                        : (const void*)k_grad32<kNiGrad32, false, false, PowP6>;
+    return hilo ? (const void*)k_grad32<kNiGrad32, true, false, PowGen>
+                : (const void*)k_grad32<kNiGrad32, false, false, PowGen>;
 }
 
 template <int KC>
 const void* frac_fn_k(int precision)
 {
     if (precision == TP_PREC_FP64) return (const void*)k_frac64<KC>;
-    if (precision == TP_PREC_FP32_HILO) return (const void*)k_frac32<kNiFrac32, KC, true>;
+    if (precision == TP_PREC_FP32_HILO || precision == TP_PREC_FP32_NEAR64)
+        return (const void*)k_frac32<kNiFrac32, KC, true>;
     return (const void*)k_frac32<kNiFrac32, KC, false>;
 }
 
@@ -895,12 +915,15 @@ hipError_t launch_pairs_energy(const PairJob* jobs, int njobs, int precision, do
         if (precision == TP_PREC_FP64) {
             if (p6) hipLaunchKernelGGL(k_energy64<PowP6>, grid, block, 0, s, jb, PowP6{});
             else hipLaunchKernelGGL(k_energy64<PowGen>, grid, block, 0, s, jb, g);
+        } else if (precision == TP_PREC_FP32_NEAR64) {
+            if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, true, PowP6>), grid, block, 0, s, jb, PowP6{});
+            else hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, true, PowGen>), grid, block, 0, s, jb, g);
         } else if (precision == TP_PREC_FP32_HILO) {
-            if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, PowP6>), grid, block, 0, s, jb, PowP6{});
-            else hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, PowGen>), grid, block, 0, s, jb, g);
+            if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, false, PowP6>), grid, block, 0, s, jb, PowP6{});
+            else hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, false, PowGen>), grid, block, 0, s, jb, g);
         } else {
-            if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, PowP6>), grid, block, 0, s, jb, PowP6{});
-            else hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, PowGen>), grid, block, 0, s, jb, g);
+            if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, false, PowP6>), grid, block, 0, s, jb, PowP6{});
+            else hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, false, PowGen>), grid, block, 0, s, jb, g);
         }
     });
 }
@@ -915,12 +938,15 @@ hipError_t launch_pairs_grad(const PairJob* jobs, int njobs, int precision, doub
         if (precision == TP_PREC_FP64) {
             if (p6) hipLaunchKernelGGL(k_grad64<PowP6>, grid, block, 0, s, jb, alpha, beta, PowP6{});
             else hipLaunchKernelGGL(k_grad64<PowGen>, grid, block, 0, s, jb, alpha, beta, g);
+        } else if (precision == TP_PREC_FP32_NEAR64) {
+            if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, true, true, PowP6>), grid, block, 0, s, jb, alpha, beta, PowP6{});
+            else hipLaunchKernelGGL((k_grad32<kNiGrad32, true, true, PowGen>), grid, block, 0, s, jb, alpha, beta, g);
         } else if (precision == TP_PREC_FP32_HILO) {
-            if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, true, PowP6>), grid, block, 0, s, jb, alpha, beta, PowP6{});
-            else hipLaunchKernelGGL((k_grad32<kNiGrad32, true, PowGen>), grid, block, 0, s, jb, alpha, beta, g);
+            if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, true, false, PowP6>), grid, block, 0, s, jb, alpha, beta, PowP6{});
+            else hipLaunchKernelGGL((k_grad32<kNiGrad32, true, false, PowGen>), grid, block, 0, s, jb, alpha, beta, g);
         } else {
-            if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, false, PowP6>), grid, block, 0, s, jb, alpha, beta, PowP6{});
-            else hipLaunchKernelGGL((k_grad32<kNiGrad32, false, PowGen>), grid, block, 0, s, jb, alpha, beta, g);
+            if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, false, false, PowP6>), grid, block, 0, s, jb, alpha, beta, PowP6{});
+            else hipLaunchKernelGGL((k_grad32<kNiGrad32, false, false, PowGen>), grid, block, 0, s, jb, alpha, beta, g);
         }
     });
 }
@@ -933,7 +959,7 @@ static hipError_t launch_frac_k(const PairJob* jobs, int njobs, int precision, d
     return for_each_batch(jobs, njobs, [&](const PairBatch& jb, dim3 grid) {
         if (precision == TP_PREC_FP64)
             hipLaunchKernelGGL(k_frac64<KC>, grid, block, 0, s, jb, expo);
-        else if (precision == TP_PREC_FP32_HILO)
+        else if (precision == TP_PREC_FP32_HILO || precision == TP_PREC_FP32_NEAR64)
             hipLaunchKernelGGL((k_frac32<kNiFrac32, KC, true>), grid, block, 0, s, jb, (float)expo);
         else
             hipLaunchKernelGGL((k_frac32<kNiFrac32, KC, false>), grid, block, 0, s, jb, (float)expo);

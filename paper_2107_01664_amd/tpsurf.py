@@ -25,7 +25,7 @@ STATUS_NAMES = {
     4: "TP_E_NONFINITE", 5: "TP_E_NOT_CONVERGED", 6: "TP_E_OUT_OF_MEMORY",
     7: "TP_E_SINGULAR_CONSTRAINTS", 8: "TP_E_DEVICE",
 }
-PREC_FP32_HILO, PREC_FP32, PREC_FP64 = 0, 1, 2
+PREC_FP32_HILO, PREC_FP32, PREC_FP64, PREC_FP32_NEAR64 = 0, 1, 2, 3
 KIND_ENERGY, KIND_GRAD, KIND_FRAC = 0, 1, 2
 
 # Every symbol the C-ABI exports (the header declares exactly these).

@@ -42,6 +42,7 @@ def test_defaults_without_gpu():
         pytest.skip("libtpsurf.so not built")
     from paper_2107_01664_amd import tpsurf
     p = tpsurf.default_params()
-    assert (p.alpha, p.beta, p.sigma, p.precision, p.cg_rtol, p.cg_maxiter) == (6.0, 12.0, -1.0, 0, 1e-10, 20000)
+    assert (p.alpha, p.beta, p.sigma, p.precision, p.cg_rtol, p.cg_maxiter) == (6.0, 12.0, -1.0, 3, 1e-10, 20000)
+    assert (p.cg_precond, p.theta, p.leaf_size) == (1, 0.0, 8)
     o = tpsurf.step_opts()
     assert o.line_search == 1 and o.max_backtracks == 30 and o.shrink == 0.5
