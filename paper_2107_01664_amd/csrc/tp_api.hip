@@ -209,9 +209,10 @@ struct tp_problem {
     int64_t nV = 0, nF = 0, cap = 0;
 
     DevBuf<double> V;
-    DevBuf<int32_t> F;
+    DevBuf<int32_t> F;              // faces in the Morton order of the first mesh's barycenters
+    DevBuf<int32_t> face_orig;      // caller's number of each stored face
     FaceData fd;
-    DevBuf<float4> fx, fl, fn;
+    DevBuf<float4> fx, fl, fn, tbox;
     DevBuf<double4> dx, dn;
     DevBuf<int> flags;
     bool geom_valid = false;     // fd describes V
@@ -256,6 +257,8 @@ struct tp_problem {
     DevBuf<unsigned long long> bh_counts;
     BhBuffers bh;
     const double* fd_V = nullptr;    // vertices the face data currently describe
+    uint64_t geom_ver = 0;           // incremented by every face-geometry launch
+    uint64_t bh_ver = ~0ull;         // geometry version the tree was built for
     double rho2 = 0.0;               // FP64 near-field radius^2: (2 x mean edge of the first mesh)^2
 
     // pinned host mirrors of device scalars, flags and CG results; multi-problem CG tables
@@ -290,6 +293,17 @@ struct tp_problem {
 };
 
 namespace {
+
+// Faces reordered: Fnew[p] = Fold[order[p]], orig[p] = order[p].
+__global__ void k_permute_faces(const int32_t* __restrict__ Fold, const int32_t* __restrict__ order, int64_t nF,
+                                int32_t* __restrict__ Fnew, int32_t* __restrict__ orig)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nF) return;
+    const int32_t s = order[p];
+    for (int c = 0; c < 3; ++c) Fnew[3 * p + c] = Fold[3 * (int64_t)s + c];
+    orig[p] = s;
+}
 
 // Per-face edge-length sums (for the mean edge length of the initial mesh).
 __global__ void k_face_edges(const double* __restrict__ V, const int32_t* __restrict__ F, int64_t nF,
@@ -360,6 +374,7 @@ tp_status alloc_faces(tp_problem* P)
     TP_TRY(P->fn.ensure(P->cap, P->stream));
     TP_TRY(P->dx.ensure(P->cap, P->stream));
     TP_TRY(P->dn.ensure(P->cap, P->stream));
+    TP_TRY(P->tbox.ensure(2 * (P->cap / kTileJ), P->stream));
     P->fd.nF = P->nF;
     P->fd.cap = P->cap;
     P->fd.fx = P->fx.p;
@@ -367,6 +382,7 @@ tp_status alloc_faces(tp_problem* P)
     P->fd.fn = P->fn.p;
     P->fd.dx = P->dx.p;
     P->fd.dn = P->dn.p;
+    P->fd.tbox = P->tbox.p;
     TP_TRY(P->flags.ensure(kNumFlags, P->stream));
     TP_HIP(hipMemsetAsync(P->flags.p, 0, sizeof(int) * kNumFlags, P->stream));
     TP_TRY(P->scal.ensure(256, P->stream));
@@ -386,6 +402,7 @@ tp_status geometry(tp_problem* P, const double* Vsrc = nullptr)
     TP_TRY(check_flags(P));
     P->geom_valid = (Vsrc == nullptr);
     P->fd_V = src;
+    ++P->geom_ver;
     return TP_OK;
 }
 
@@ -732,14 +749,24 @@ tp_status ensure_bh(tp_problem* P)
     return TP_OK;
 }
 
+// The Morton tree of the current face data (built once per geometry).
+tp_status ensure_tree(tp_problem* P)
+{
+    TP_TRY(ensure_bh(P));
+    if (P->bh_ver != P->geom_ver) {
+        TP_HIP(launch_bh_build(P->bh, P->fd_V, P->F.p, P->face_orig.p, P->nF, P->prm.leaf_size, P->fd, P->stream));
+        P->bh_ver = P->geom_ver;
+    }
+    return TP_OK;
+}
+
 // E_BH -> scal[slot]; with dE, the differential of E_BH into dE (nV x 3).  The face data
 // must describe P->fd_V (the tree is built from it).
 tp_status enqueue_bh(tp_problem* P, double* dE, int slot)
 {
     hipStream_t s = P->stream;
-    TP_TRY(ensure_bh(P));
+    TP_TRY(ensure_tree(P));
     const int leaf = P->prm.leaf_size;
-    TP_HIP(launch_bh_build(P->bh, P->fd_V, P->F.p, P->nF, leaf, P->fd, s));
     if (dE) {
         TP_TRY(ensure_vf(P));
         TP_TRY(P->gface.ensure((size_t)7 * P->nF, s));
@@ -763,20 +790,23 @@ double gradient_energy(const tp_problem* P, double v)
 
 bool near_field(const tp_problem* P) { return P->prm.precision == TP_PREC_FP32_NEAR64; }
 
-// The FP64 near-field slice (index `slice` of the partial buffer, nacc accumulators) of
-// every problem of the batch that uses it.
+// The FP64 near-field slice (index n_split of the partial buffer, nacc accumulators) of
+// every problem of the batch that uses it, in one launch.
 tp_status enqueue_near(const Batch& B, const std::vector<PairPlan>& plans, int nacc, bool grad)
 {
+    std::vector<PairJob> jobs;
     for (size_t m = 0; m < B.size(); ++m) {
         tp_problem* P = B[m];
         if (!near_field(P)) continue;
         const PairPlan& pl = plans[m];
-        TP_TRY(ensure_bh(P));
-        TP_HIP(launch_bh_build(P->bh, P->fd_V, P->F.p, P->nF, P->prm.leaf_size, P->fd, P->stream));
-        double* slice = P->part.p + (size_t)pl.n_split * nacc * pl.irows;
-        TP_HIP(launch_near64(P->bh, P->nF, P->prm.leaf_size, P->rho2, P->fd, P->prm.alpha, P->prm.beta, grad, slice,
-                             pl.irows, P->stream));
+        PairJob J = make_pair_job(P->fd, pl, P->part.p + (size_t)pl.n_split * nacc * pl.irows);
+        J.n_itiles = (int)((P->nF + near_block_faces() - 1) / near_block_faces());
+        J.tiles_per_split = J.ntiles_j;
+        J.rho2 = (float)P->rho2;
+        jobs.push_back(J);
     }
+    if (jobs.empty()) return TP_OK;
+    TP_HIP(launch_near64(jobs.data(), (int)jobs.size(), B[0]->prm.alpha, B[0]->prm.beta, grad, B[0]->stream));
     return TP_OK;
 }
 
@@ -1195,6 +1225,25 @@ tp_status create_problem(const double* V, int64_t nV, const int32_t* F, int64_t 
         return bail(fail(TP_E_DEVICE, "index check launch failed"));
     if ((st = check_flags(P)) != TP_OK) return bail(st);
     if ((st = geometry(P)) != TP_OK) return bail(st);
+    // store the faces in the Morton order of their barycenters: face tiles become compact
+    // patches (the near-field tile test and the tree build rely on it); results do not
+    // depend on the stored order beyond rounding, and the tree breaks ties by the caller's
+    // face numbers
+    {
+        DevBuf<int32_t> Fold;
+        if ((st = ensure_bh(P)) != TP_OK) return bail(st);
+        if ((st = Fold.ensure(3 * nF, stream)) != TP_OK) return bail(st);
+        if ((st = P->face_orig.ensure(nF, stream)) != TP_OK) return bail(st);
+        if (hipMemcpyAsync(Fold.p, P->F.p, sizeof(int32_t) * 3 * nF, hipMemcpyDeviceToDevice, stream) != hipSuccess ||
+            launch_morton_order(P->bh, P->fd, nF, nullptr, stream) != hipSuccess)
+            return bail(fail(TP_E_DEVICE, "face ordering failed"));
+        hipLaunchKernelGGL(k_permute_faces, dim3((unsigned)((nF + 255) / 256)), dim3(256), 0, stream, Fold.p,
+                           P->bh.order, nF, P->F.p, P->face_orig.p);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(stream) != hipSuccess)
+            return bail(fail(TP_E_DEVICE, "face ordering failed"));
+        P->geom_valid = false;
+        if ((st = geometry(P)) != TP_OK) return bail(st);
+    }
     if (P->prm.precision == TP_PREC_FP32_NEAR64) {
         if ((st = P->edge.ensure(P->nF, stream)) != TP_OK) return bail(st);
         hipLaunchKernelGGL(k_face_edges, dim3((unsigned)((nF + 255) / 256)), dim3(256), 0, stream, P->V.p, P->F.p,
@@ -1432,6 +1481,7 @@ tp_status step_group(std::vector<StepState*>& G)
             TP_HIP(launch_axpy_block3(P->nV, P->V.p, 3, 1.0, P->dir.p, 3, 1, &cf, &c0, P->Vt.p, 3, s));
             TP_HIP(launch_face_geom(P->Vt.p, P->nV, P->F.p, P->nF, P->fd, P->flags.p, s));
             P->fd_V = P->Vt.p;
+            ++P->geom_ver;
             P->geom_valid = false;
             BS.push_back(P);
         }
@@ -1499,6 +1549,7 @@ tp_status step_group(std::vector<StepState*>& G)
         P->cotan_valid = false;
         TP_HIP(launch_face_geom(P->V.p, P->nV, P->F.p, P->nF, P->fd, P->flags.p, s));
         P->fd_V = P->V.p;
+        ++P->geom_ver;
         TP_TRY(enqueue_area_volume(P, P->V.p));
         BF.push_back(P);
         fin.push_back(S);

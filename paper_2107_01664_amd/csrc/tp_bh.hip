@@ -1,8 +1,8 @@
 // Barnes-Hut approximation of the energy and its differential (Sec. 4) on gfx950.
 //
 // Tree.  Faces are sorted by the 30-bit Morton code of their barycenters (10 bits per
-// coordinate, quantized on the bounding box of all barycenters; ties by face index, so
-// the 64-bit keys code << 32 | face are unique).  Leaves hold `leaf` consecutive sorted
+// coordinate, quantized on the bounding box of all barycenters), ties by the caller's face
+// number (faces are stored internally in the Morton order of the first mesh).  Leaves hold `leaf` consecutive sorted
 // faces and the internal nodes form a perfect binary tree over the leaves in heap order
 // (node 1 is the root, node i has children 2i and 2i + 1, the leaves are nodes
 // P .. 2P - 1).  The tree is therefore fixed by the sort alone: no pointer chasing, and
@@ -111,26 +111,26 @@ __global__ __launch_bounds__(1024) void k_bh_bbox(const double4* __restrict__ dx
     if (threadIdx.x < 6) box[threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// Keys (Morton code << 32 | caller's face number) and the internal face index as value;
+// the caller's numbers make the order independent of how faces are stored.
 __global__ void k_bh_keys(const double4* __restrict__ dx, int64_t nF, const double* __restrict__ box,
-                          uint64_t* __restrict__ keys)
+                          const int32_t* __restrict__ orig, uint64_t* __restrict__ keys,
+                          int32_t* __restrict__ idx)
 {
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= nF) return;
     const double4 X = dx[s];
     const uint32_t code = (spread10(quant10(X.x, box[0], box[3])) << 2) |
-                          (spread10(quant10(X.y, box[1], box[4])) << 1) |
-                          spread10(quant10(X.z, box[2], box[5]));
-    keys[s] = ((uint64_t)code << 32) | (uint64_t)s;
+                          (spread10(quant10(X.y, box[1], box[4])) << 1) | spread10(quant10(X.z, box[2], box[5]));
+    keys[s] = ((uint64_t)code << 32) | (uint64_t)(uint32_t)(orig ? orig[s] : (int32_t)s);
+    idx[s] = (int32_t)s;
 }
 
-__global__ void k_bh_order(const uint64_t* __restrict__ keys, int64_t nF, int32_t* __restrict__ order,
-                           int32_t* __restrict__ pos)
+__global__ void k_bh_pos(const int32_t* __restrict__ order, int64_t nF, int32_t* __restrict__ pos)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nF) return;
-    const int32_t s = (int32_t)(keys[p] & 0xffffffffull);
-    order[p] = s;
-    pos[s] = (int32_t)p;
+    pos[order[p]] = (int32_t)p;
 }
 
 // Leaf nodes P + l: sums over the member faces in sorted order.
@@ -163,27 +163,11 @@ __global__ void k_bh_leaves(int64_t nF, int leaf, int64_t P, const int32_t* __re
     }
 }
 
-// Internal nodes [n0, n1) from their children.
-__global__ void k_bh_level(int64_t n0, int64_t n1, double* __restrict__ na, double* __restrict__ nsx,
-                           double* __restrict__ nlo, double* __restrict__ nhi)
+__device__ __forceinline__ void bh_node_finish(int64_t node, const double* __restrict__ na,
+                                               const double* __restrict__ nsx, const double* __restrict__ nlo,
+                                               const double* __restrict__ nhi, double* __restrict__ nX,
+                                               double* __restrict__ nr2)
 {
-    const int64_t node = n0 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (node >= n1) return;
-    const int64_t L = 2 * node, R = 2 * node + 1;
-    na[node] = na[L] + na[R];
-    for (int m = 0; m < 3; ++m) {
-        nsx[3 * node + m] = nsx[3 * L + m] + nsx[3 * R + m];
-        nlo[3 * node + m] = nlo[3 * L + m] < nlo[3 * R + m] ? nlo[3 * L + m] : nlo[3 * R + m];
-        nhi[3 * node + m] = nhi[3 * L + m] > nhi[3 * R + m] ? nhi[3 * L + m] : nhi[3 * R + m];
-    }
-}
-
-__global__ void k_bh_nodefinish(int64_t M, const double* __restrict__ na, const double* __restrict__ nsx,
-                                const double* __restrict__ nlo, const double* __restrict__ nhi,
-                                double* __restrict__ nX, double* __restrict__ nr2)
-{
-    const int64_t node = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (node >= M || node == 0) return;
     const double a = na[node];
     if (!(a > 0.0)) {
         nr2[node] = 0.0;
@@ -199,6 +183,28 @@ __global__ void k_bh_nodefinish(int64_t M, const double* __restrict__ na, const 
         r2 = r2 + w * w;
     }
     nr2[node] = r2;
+}
+
+// Internal nodes level by level (children before parents) in one workgroup, then the
+// node barycenters and radii of all nodes.
+__global__ __launch_bounds__(1024) void k_bh_levels(int64_t P, double* __restrict__ na, double* __restrict__ nsx,
+                                                    double* __restrict__ nlo, double* __restrict__ nhi,
+                                                    double* __restrict__ nX, double* __restrict__ nr2)
+{
+    for (int64_t n0 = P / 2; n0 >= 1; n0 /= 2) {
+        for (int64_t node = n0 + threadIdx.x; node < 2 * n0; node += blockDim.x) {
+            const int64_t L = 2 * node, R = 2 * node + 1;
+            na[node] = na[L] + na[R];
+            for (int m = 0; m < 3; ++m) {
+                nsx[3 * node + m] = nsx[3 * L + m] + nsx[3 * R + m];
+                nlo[3 * node + m] = nlo[3 * L + m] < nlo[3 * R + m] ? nlo[3 * L + m] : nlo[3 * R + m];
+                nhi[3 * node + m] = nhi[3 * L + m] > nhi[3 * R + m] ? nhi[3 * L + m] : nhi[3 * R + m];
+            }
+        }
+        __syncthreads();
+    }
+    for (int64_t node = 1 + threadIdx.x; node < 2 * P; node += blockDim.x)
+        bh_node_finish(node, na, nsx, nlo, nhi, nX, nr2);
 }
 
 #pragma clang fp contract(fast)
@@ -390,167 +396,7 @@ __global__ void k_bh_assemble(int64_t nF, int leaf, int64_t P, const int32_t* __
     gface[6 * gstride + t] = ga;
 }
 
-// ------------------------------------------------------------------ FP64 near field
-
-struct NearArgs {
-    int64_t nF, P;
-    int leaf;
-    double prune2;        // subtrees farther than this (squared, from X_S) hold no near pair
-    float rho2;           // a pair is near when its FP32 hi+lo squared distance is < rho2
-    double alpha, beta;
-    const int32_t* order;
-    const float4* fx;
-    const float4* fl;
-    const double4* dx;
-    const double4* dn;
-    const double* na;
-    const double* nlo;
-    const double* nhi;
-    double* out;
-    int64_t irows;
-};
-
-// FP64 kernel of one ordered pair: K and K r2 / q (0 for q = 0).
-template <bool GEN>
-__device__ __forceinline__ void kg64(double q, double r2, double inv, double alpha, double beta, double& K,
-                                     double& Kqr)
-{
-    if (!GEN) {
-        const double u = q * inv, u2 = u * u, u4 = u2 * u2;
-        K = u4 * u2;
-        Kqr = u4 * u;
-    } else {
-        if (q == 0.0) {
-            K = 0.0;
-            Kqr = 0.0;
-            return;
-        }
-        Kqr = copysign(pow(fabs(q), alpha - 1.0) * pow(r2, 1.0 - 0.5 * beta), q);
-        K = Kqr * q * inv;
-    }
-}
-
-// One thread per face (Morton order): the pairs (S, T) that the FP32 kernels leave out,
-// in FP64, with the same per-face accumulators and epilogue as the all-pairs kernels.
-template <bool GEN, bool GRAD>
-__global__ __launch_bounds__(256) void k_near64(NearArgs A)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= A.nF) return;
-    const int32_t s = A.order[p];
-    const float4 sh = A.fx[s], sl = A.fl[s];
-    const double4 X = A.dx[s], Nn = A.dn[s];
-    double c[11];
-    for (int m = 0; m < 11; ++m) c[m] = 0.0;
-    double e = 0.0;
-    int64_t node = 1;
-    for (;;) {
-        bool down = false;
-        if (A.na[node] > 0.0) {
-            double d2 = 0.0;
-            const double xs[3] = {X.x, X.y, X.z};
-            for (int m = 0; m < 3; ++m) {
-                const double g1 = A.nlo[3 * node + m] - xs[m], g2 = xs[m] - A.nhi[3 * node + m];
-                double g = g1 > g2 ? g1 : g2;
-                g = g < 0.0 ? 0.0 : g;
-                d2 += g * g;
-            }
-            if (d2 <= A.prune2) {
-                if (node >= A.P) {
-                    const int64_t l = node - A.P;
-                    const int64_t q1 = min((l + 1) * (int64_t)A.leaf, A.nF);
-                    for (int64_t qq = l * A.leaf; qq < q1; ++qq) {
-                        const int32_t t = A.order[qq];
-                        if (t == s) continue;
-                        const float4 th = A.fx[t], tl = A.fl[t];
-                        const float fdx = (sh.x - th.x) + (sl.x - tl.x);
-                        const float fdy = (sh.y - th.y) + (sl.y - tl.y);
-                        const float fdz = (sh.z - th.z) + (sl.z - tl.z);
-                        const float r2f = __builtin_fmaf(fdz, fdz, __builtin_fmaf(fdy, fdy, fdx * fdx));
-                        if (!(r2f < A.rho2)) continue;
-                        const double4 Y = A.dx[t], Nt = A.dn[t];
-                        const double dx = X.x - Y.x, dy = X.y - Y.y, dz = X.z - Y.z;
-                        const double r2 = dx * dx + dy * dy + dz * dz;
-                        const double inv = 1.0 / r2;
-                        const double q = Nn.x * dx + Nn.y * dy + Nn.z * dz;
-                        double K, Kqr;
-                        kg64<GEN>(q, r2, inv, A.alpha, A.beta, K, Kqr);
-                        if (!GRAD) {
-                            e += K * Y.w;
-                            continue;
-                        }
-                        const double qp = Nt.x * dx + Nt.y * dy + Nt.z * dz;
-                        double Kp, Kpqr;
-                        kg64<GEN>(qp, r2, inv, A.alpha, A.beta, Kp, Kpqr);
-                        const double tt = Y.w * inv;
-                        const double aq = Kqr * tt, ap = Kpqr * tt, KK = K + Kp, cc = KK * tt;
-                        c[0] += aq;
-                        c[1] += ap * Nt.x;
-                        c[2] += ap * Nt.y;
-                        c[3] += ap * Nt.z;
-                        c[4] += cc * dx;
-                        c[5] += cc * dy;
-                        c[6] += cc * dz;
-                        c[7] += aq * dx;
-                        c[8] += aq * dy;
-                        c[9] += aq * dz;
-                        c[10] += KK * Y.w;
-                    }
-                } else {
-                    down = true;
-                }
-            }
-        }
-        if (down) {
-            node = 2 * node;
-            continue;
-        }
-        while (node & 1) node >>= 1;
-        if (node == 0) break;
-        node += 1;
-    }
-    if (!GRAD) {
-        A.out[s] = e;
-        return;
-    }
-    const double aS = X.w, al = A.alpha, be = A.beta;
-    double o[7];
-    o[0] = aS * (al * (Nn.x * c[0] + c[1]) - be * c[4]);
-    o[1] = aS * (al * (Nn.y * c[0] + c[2]) - be * c[5]);
-    o[2] = aS * (al * (Nn.z * c[0] + c[3]) - be * c[6]);
-    o[3] = aS * al * c[7];
-    o[4] = aS * al * c[8];
-    o[5] = aS * al * c[9];
-    o[6] = c[10];
-    for (int m = 0; m < 7; ++m) A.out[m * A.irows + s] = o[m];
-}
-
 }  // namespace
-
-hipError_t launch_near64(const BhBuffers& b, int64_t nF, int leaf, double rho2, const FaceData& fd,
-                         double alpha, double beta, bool grad, double* out, int64_t irows, hipStream_t s)
-{
-    int64_t P = 0;
-    (void)bh_node_count(nF, leaf, &P);
-    NearArgs A;
-    A.nF = nF; A.P = P; A.leaf = leaf;
-    A.prune2 = rho2 * 1.001 + 1e-300;      // the FP32 distance may be short of the exact one
-    A.rho2 = (float)rho2;
-    A.alpha = alpha; A.beta = beta;
-    A.order = b.order; A.fx = fd.fx; A.fl = fd.fl; A.dx = fd.dx; A.dn = fd.dn;
-    A.na = b.na; A.nlo = b.nlo; A.nhi = b.nhi;
-    A.out = out; A.irows = irows;
-    const dim3 grid((unsigned)((nF + 255) / 256)), block(256);
-    const bool gen = !(alpha == 6.0 && beta == 12.0);
-    if (grad) {
-        if (gen) hipLaunchKernelGGL((k_near64<true, true>), grid, block, 0, s, A);
-        else hipLaunchKernelGGL((k_near64<false, true>), grid, block, 0, s, A);
-    } else {
-        if (gen) hipLaunchKernelGGL((k_near64<true, false>), grid, block, 0, s, A);
-        else hipLaunchKernelGGL((k_near64<false, false>), grid, block, 0, s, A);
-    }
-    return hipGetLastError();
-}
 
 size_t bh_node_count(int64_t nF, int leaf, int64_t* P_out)
 {
@@ -564,35 +410,37 @@ size_t bh_node_count(int64_t nF, int leaf, int64_t* P_out)
 size_t bh_sort_temp_bytes(int64_t nF)
 {
     size_t bytes = 0;
-    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                                            (int)nF, 0, 62);
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                             (const int32_t*)nullptr, (int32_t*)nullptr, (int)nF, 0, 62);
     return bytes;
 }
 
-hipError_t launch_bh_build(const BhBuffers& b, const double* V, const int32_t* F, int64_t nF, int leaf,
-                           const FaceData& fd, hipStream_t s)
+hipError_t launch_morton_order(const BhBuffers& b, const FaceData& fd, int64_t nF, const int32_t* orig,
+                               hipStream_t s)
 {
-    int64_t P = 0;
-    const int64_t M = (int64_t)bh_node_count(nF, leaf, &P);
     const unsigned g = (unsigned)((nF + 255) / 256);
-    hipLaunchKernelGGL(k_bh_faceprep, dim3(g), dim3(256), 0, s, V, F, nF, fd.dx, b.flo, b.fhi, b.fr2);
     hipLaunchKernelGGL(k_bh_bbox, dim3(1), dim3(1024), 0, s, fd.dx, nF, b.box);
-    hipLaunchKernelGGL(k_bh_keys, dim3(g), dim3(256), 0, s, fd.dx, nF, b.box, b.keys_in);
+    // values in b.pos, sorted values into b.order
+    hipLaunchKernelGGL(k_bh_keys, dim3(g), dim3(256), 0, s, fd.dx, nF, b.box, orig, b.keys_in, b.pos);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     size_t tb = b.sort_bytes;
-    e = hipcub::DeviceRadixSort::SortKeys(b.sort_tmp, tb, b.keys_in, b.keys_out, (int)nF, 0, 62, s);
+    return hipcub::DeviceRadixSort::SortPairs(b.sort_tmp, tb, b.keys_in, b.keys_out, b.pos, b.order, (int)nF, 0, 62, s);
+}
+
+hipError_t launch_bh_build(const BhBuffers& b, const double* V, const int32_t* F, const int32_t* orig, int64_t nF,
+                           int leaf, const FaceData& fd, hipStream_t s)
+{
+    int64_t P = 0;
+    (void)bh_node_count(nF, leaf, &P);
+    const unsigned g = (unsigned)((nF + 255) / 256);
+    hipLaunchKernelGGL(k_bh_faceprep, dim3(g), dim3(256), 0, s, V, F, nF, fd.dx, b.flo, b.fhi, b.fr2);
+    hipError_t e = launch_morton_order(b, fd, nF, orig, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bh_order, dim3(g), dim3(256), 0, s, b.keys_out, nF, b.order, b.pos);
+    hipLaunchKernelGGL(k_bh_pos, dim3(g), dim3(256), 0, s, b.order, nF, b.pos);
     hipLaunchKernelGGL(k_bh_leaves, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, nF, leaf, P, b.order,
                        fd.dx, b.flo, b.fhi, b.na, b.nsx, b.nlo, b.nhi);
-    for (int64_t n0 = P / 2; n0 >= 1; n0 /= 2) {
-        const int64_t cnt = n0;   // nodes [n0, 2 n0)
-        hipLaunchKernelGGL(k_bh_level, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, n0, 2 * n0, b.na,
-                           b.nsx, b.nlo, b.nhi);
-    }
-    hipLaunchKernelGGL(k_bh_nodefinish, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, M, b.na, b.nsx,
-                       b.nlo, b.nhi, b.nX, b.nr2);
+    hipLaunchKernelGGL(k_bh_levels, dim3(1), dim3(1024), 0, s, P, b.na, b.nsx, b.nlo, b.nhi, b.nX, b.nr2);
     return hipGetLastError();
 }
 

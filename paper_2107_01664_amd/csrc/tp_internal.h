@@ -65,6 +65,8 @@ struct FaceData {
     float4* fn = nullptr;    // (N.x, N.y, N.z, 0)        FP32
     double4* dx = nullptr;   // (X.x, X.y, X.z, a)        FP64
     double4* dn = nullptr;   // (N.x, N.y, N.z, 0)        FP64
+    float4* tbox = nullptr;  // per kTileJ faces: (lo, hi) boxes of the FP32 barycenters of the
+                             // real faces (2 entries per tile; empty box for padding tiles)
 };
 
 // Pair-kernel launch geometry for one problem size.
@@ -104,6 +106,7 @@ struct PairJob {
     int64_t irows = 0;
     int n_itiles = 0, tiles_per_split = 0, ntiles_j = 0, block0 = 0;
     float rho2 = 0.f;               // TP_PREC_FP32_NEAR64: pairs with r2 < rho2 are left out
+    const float4* tbox = nullptr;   // tile boxes (FaceData::tbox)
 };
 constexpr int kMaxPairJobs = 16;
 PairJob make_pair_job(const FaceData& fd, const PairPlan& pl, double* part, const void* ub = nullptr);
@@ -276,22 +279,26 @@ struct BhBuffers {
 };
 size_t bh_node_count(int64_t nF, int leaf, int64_t* P_out);
 size_t bh_sort_temp_bytes(int64_t nF);
-// Tree of the faces described by fd, whose vertices are V.
-hipError_t launch_bh_build(const BhBuffers& b, const double* V, const int32_t* F, int64_t nF, int leaf,
-                           const FaceData& fd, hipStream_t s);
+// Faces sorted by (Morton code of the barycenter, orig[face] or the face index when orig is
+// NULL): sorted internal indices into b.order (uses b.box, b.keys_*, b.pos, b.sort_tmp).
+hipError_t launch_morton_order(const BhBuffers& b, const FaceData& fd, int64_t nF, const int32_t* orig,
+                               hipStream_t s);
+// Tree of the faces described by fd, whose vertices are V; orig = the caller's face numbers.
+hipError_t launch_bh_build(const BhBuffers& b, const double* V, const int32_t* F, const int32_t* orig, int64_t nF,
+                           int leaf, const FaceData& fd, hipStream_t s);
 // E_BH rows into b.eS and, with grad, the per-face partial derivatives into gface
 // ([7][gstride]: dE/dX, dE/dN, dE/da).
 hipError_t launch_bh_eval(const BhBuffers& b, int64_t nF, int leaf, double theta, int precision, double alpha,
                           double beta, const FaceData& fd, bool grad, double* gface, int64_t gstride,
                           hipStream_t s);
 
-// FP64 near field (TP_PREC_FP32_NEAR64): for every face S, the pairs (S, T), T != S, whose
-// FP32 hi+lo barycenter distance satisfies r2 < rho2 (the pairs the FP32 kernels leave
-// out), found with the Barnes-Hut tree of the current face data, summed in FP64.  With
-// grad, out is one [7][irows] slice of the gradient partials; else one [irows] slice of
-// the energy partials.
-hipError_t launch_near64(const BhBuffers& b, int64_t nF, int leaf, double rho2, const FaceData& fd,
-                         double alpha, double beta, bool grad, double* out, int64_t irows, hipStream_t s);
+// FP64 near field (TP_PREC_FP32_NEAR64), as one launch over the problems of a batch: for
+// every face S, the pairs (S, T), T != S, whose FP32 hi+lo squared barycenter distance is
+// below the job's rho2 (exactly the pairs the FP32 kernels leave out), summed in FP64 into
+// the job's partial slice ([7][irows] with grad, else [irows]).  Only j-tiles whose box lies
+// within the near radius of the i-range are visited.
+hipError_t launch_near64(const PairJob* jobs, int njobs, double alpha, double beta, bool grad, hipStream_t s);
+int near_block_faces();           // faces S per near-field workgroup (n_itiles of a near job)
 
 // ------------------------------------------------------------------ device-side sync
 

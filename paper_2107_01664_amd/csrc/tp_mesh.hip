@@ -80,11 +80,52 @@ __global__ void k_face_geom(const double* __restrict__ V, int64_t nV, const int3
     write_face(fd, s, X[0], X[1], X[2], c0 / cn, c1 / cn, c2 / cn, 0.5 * cn);
 }
 
+// Boxes of the FP32 barycenters (hi parts) of the real faces of every tile of kTileJ
+// faces; a tile of padding faces gets an empty box (lo = +inf, hi = -inf).
+__global__ __launch_bounds__(kTileJ) void k_tile_boxes(FaceData fd)
+{
+    __shared__ float sh[6][kTileJ];
+    const int64_t s = (int64_t)blockIdx.x * kTileJ + threadIdx.x;
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    if (s < fd.nF) {
+        const float4 x = fd.fx[s];
+        lo[0] = hi[0] = x.x;
+        lo[1] = hi[1] = x.y;
+        lo[2] = hi[2] = x.z;
+    }
+    for (int m = 0; m < 3; ++m) {
+        sh[m][threadIdx.x] = lo[m];
+        sh[3 + m][threadIdx.x] = hi[m];
+    }
+    __syncthreads();
+    for (int w = kTileJ / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int m = 0; m < 3; ++m) {
+                sh[m][threadIdx.x] = fminf(sh[m][threadIdx.x], sh[m][threadIdx.x + w]);
+                sh[3 + m][threadIdx.x] = fmaxf(sh[3 + m][threadIdx.x], sh[3 + m][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        fd.tbox[2 * blockIdx.x] = make_float4(sh[0][0], sh[1][0], sh[2][0], 0.f);
+        fd.tbox[2 * blockIdx.x + 1] = make_float4(sh[3][0], sh[4][0], sh[5][0], 0.f);
+    }
+}
+
+static hipError_t launch_tile_boxes(const FaceData& fd, hipStream_t s)
+{
+    if (!fd.tbox) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_boxes, dim3((unsigned)(fd.cap / kTileJ)), dim3(kTileJ), 0, s, fd);
+    return hipGetLastError();
+}
+
 hipError_t launch_face_geom(const double* V, int64_t nV, const int32_t* F, int64_t nF,
                             const FaceData& fd, int* flags, hipStream_t s)
 {
     hipLaunchKernelGGL(k_face_geom, dim3(nblocks(fd.cap)), dim3(256), 0, s, V, nV, F, nF, fd, flags);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_tile_boxes(fd, s);
 }
 
 __global__ void k_face_from_quantities(const double* __restrict__ X, const double* __restrict__ N,
@@ -112,7 +153,9 @@ hipError_t launch_face_from_quantities(const double* X, const double* N, const d
                                        int64_t nF, const FaceData& fd, int* flags, hipStream_t s)
 {
     hipLaunchKernelGGL(k_face_from_quantities, dim3(nblocks(fd.cap)), dim3(256), 0, s, X, N, a, nF, fd, flags);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_tile_boxes(fd, s);
 }
 
 // ------------------------------------------------------------------ vertex-face incidence

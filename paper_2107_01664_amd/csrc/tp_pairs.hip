@@ -142,6 +142,31 @@ __device__ __forceinline__ bool tile_hits_diag(int64_t j0, int64_t ibase, int is
     return j0 < ibase + ispan && j0 + kTileJ > ibase;
 }
 
+// Box of the i-range [ibase, ibase + ispan) from the tile boxes.
+__device__ __forceinline__ void irange_box(const float4* tbox, int64_t ibase, int ispan, float4& lo, float4& hi)
+{
+    lo = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
+    hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
+    for (int64_t t = ibase / kTileJ; t < (ibase + ispan) / kTileJ; ++t) {
+        const float4 a = tbox[2 * t], b = tbox[2 * t + 1];
+        lo = make_float4(fminf(lo.x, a.x), fminf(lo.y, a.y), fminf(lo.z, a.z), 0.f);
+        hi = make_float4(fmaxf(hi.x, b.x), fmaxf(hi.y, b.y), fmaxf(hi.z, b.z), 0.f);
+    }
+}
+
+// Can a pair of the i-range box and j-tile jt be closer than the near-field radius?  The
+// boxes hold the FP32 barycenters, within rounding of the hi+lo distances, so the test
+// uses a 1 % margin.
+__device__ __forceinline__ bool tile_may_be_near(const float4& ilo, const float4& ihi, const float4* tbox,
+                                                 int jt, float rho2)
+{
+    const float4 a = tbox[2 * jt], b = tbox[2 * jt + 1];
+    const float gx = fmaxf(fmaxf(a.x - ihi.x, ilo.x - b.x), 0.f);
+    const float gy = fmaxf(fmaxf(a.y - ihi.y, ilo.y - b.y), 0.f);
+    const float gz = fmaxf(fmaxf(a.z - ihi.z, ilo.z - b.z), 0.f);
+    return gx * gx + gy * gy + gz * gz <= 1.01f * rho2;
+}
+
 // ============================================================== energy (FP32)
 
 // Squared FP32 distance of a pair, in one fixed sequence of operations (the FP64 near
@@ -217,6 +242,8 @@ __global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
         }
         acc[r] = 0.0;
     }
+    float4 ilo, ihi;
+    if (NEAR) irange_box(J.tbox, ibase, kBlock * NI, ilo, ihi);
     for (int jt = jt0; jt < jt1; ++jt) {
         const int64_t j0 = (int64_t)jt * kTileJ;
         __syncthreads();
@@ -227,8 +254,10 @@ __global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
         for (int r = 0; r < NI; ++r) c[r] = 0.f;
         if (tile_hits_diag(j0, ibase, kBlock * NI))
             energy_tile32<true, NI, HILO, NEAR>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
-        else
+        else if (NEAR && tile_may_be_near(ilo, ihi, J.tbox, jt, J.rho2))
             energy_tile32<false, NI, HILO, NEAR>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
+        else
+            energy_tile32<false, NI, HILO, false>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
 #pragma unroll
         for (int r = 0; r < NI; ++r) acc[r] += (double)c[r];
     }
@@ -341,6 +370,8 @@ __global__ __launch_bounds__(kBlock) void k_grad32(PairBatch jb, double alpha, d
 #pragma unroll
         for (int m = 0; m < kGradAcc; ++m) acc[r][m] = 0.0;
     }
+    float4 ilo, ihi;
+    if (NEAR) irange_box(J.tbox, ibase, kBlock * NI, ilo, ihi);
     for (int jt = jt0; jt < jt1; ++jt) {
         const int64_t j0 = (int64_t)jt * kTileJ;
         __syncthreads();
@@ -353,8 +384,10 @@ __global__ __launch_bounds__(kBlock) void k_grad32(PairBatch jb, double alpha, d
             for (int m = 0; m < kGradAcc; ++m) c[r][m] = 0.f;
         if (tile_hits_diag(j0, ibase, kBlock * NI))
             grad_tile32<true, NI, HILO, NEAR>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
-        else
+        else if (NEAR && tile_may_be_near(ilo, ihi, J.tbox, jt, J.rho2))
             grad_tile32<false, NI, HILO, NEAR>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
+        else
+            grad_tile32<false, NI, HILO, false>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
 #pragma unroll
         for (int r = 0; r < NI; ++r)
 #pragma unroll
@@ -685,6 +718,154 @@ __global__ __launch_bounds__(kBlock) void k_frac64(PairBatch jb, double expo)
     for (int cc = 0; cc < KC; ++cc) part[((int64_t)bs * KC + cc) * irows + Si] = acc[cc];
 }
 
+// ============================================================== FP64 near field
+//
+// A pair (S, T), T != S, is near when its FP32 hi+lo squared distance, formed exactly as
+// in the FP32 kernels, is below rho2; near pairs are summed in FP64 with the same
+// accumulators and epilogue as the all-pairs kernels (row ownership: S collects the (S,T)
+// and (T,S) terms).  Only j-tiles whose box lies within the near radius of the i-range box
+// are visited.
+
+template <bool GEN>
+__device__ __forceinline__ void kg64(double q, double r2, double inv, double alpha, double beta, double& K,
+                                     double& Kqr)
+{
+    if (!GEN) {
+        const double u = q * inv, u2 = u * u, u4 = u2 * u2;
+        K = u4 * u2;
+        Kqr = u4 * u;
+    } else if (q == 0.0) {
+        K = 0.0;
+        Kqr = 0.0;
+    } else {
+        Kqr = copysign(pow(fabs(q), alpha - 1.0) * pow(r2, 1.0 - 0.5 * beta), q);
+        K = Kqr * q * inv;
+    }
+}
+
+constexpr int kNearChunk = 1024;   // j-tiles tested per pass
+constexpr int kNearI = 64;         // faces S per workgroup (one wave)
+
+// Workgroup = one wave of kNearI faces S.  Candidate j-tiles are tested in chunks by all
+// lanes at once (flags in LDS) and visited in increasing order; in a visited tile every
+// lane first forms its near mask over the kTileJ faces with FP32 arithmetic only, then
+// evaluates its own near pairs in FP64 (in increasing T).
+template <bool GEN, bool GRAD>
+__global__ __launch_bounds__(kNearI) void k_near64(PairBatch jb, double alpha, double beta)
+{
+    __shared__ float4 s_h[kTileJ], s_l[kTileJ];
+    __shared__ double4 s_x[kTileJ], s_n[kTileJ];
+    __shared__ unsigned char s_flag[kNearChunk];
+    const PairJob J = pick_job(jb);
+    const int64_t ibase = (int64_t)((int)blockIdx.x - J.block0) * kNearI;
+    const int64_t S = ibase + threadIdx.x;
+    const float4 sh = J.fx[S], sl = J.fl[S];
+    const double4 X = J.dx[S], Nn = J.dn[S];
+    // box of this wave's barycenters (FP32 hi parts of real faces)
+    float4 ilo = make_float4(INFINITY, INFINITY, INFINITY, 0.f), ihi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
+    if (sh.w != 0.f) {
+        ilo = make_float4(sh.x, sh.y, sh.z, 0.f);
+        ihi = ilo;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        ilo.x = fminf(ilo.x, __shfl_xor(ilo.x, off)); ilo.y = fminf(ilo.y, __shfl_xor(ilo.y, off));
+        ilo.z = fminf(ilo.z, __shfl_xor(ilo.z, off)); ihi.x = fmaxf(ihi.x, __shfl_xor(ihi.x, off));
+        ihi.y = fmaxf(ihi.y, __shfl_xor(ihi.y, off)); ihi.z = fmaxf(ihi.z, __shfl_xor(ihi.z, off));
+    }
+    double c[11];
+#pragma unroll
+    for (int m = 0; m < 11; ++m) c[m] = 0.0;
+    double e = 0.0;
+    for (int c0 = 0; c0 < J.ntiles_j; c0 += kNearChunk) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < kNearChunk; q += kNearI) {
+            const int jt = c0 + q;
+            s_flag[q] = (jt < J.ntiles_j && tile_may_be_near(ilo, ihi, J.tbox, jt, J.rho2)) ? 1 : 0;
+        }
+        __syncthreads();
+        const int cend = min(kNearChunk, J.ntiles_j - c0);
+        for (int qt = 0; qt < cend; ++qt) {
+            if (!s_flag[qt]) continue;
+            const int64_t j0 = (int64_t)(c0 + qt) * kTileJ;
+            __syncthreads();
+            for (int q = threadIdx.x; q < kTileJ; q += kNearI) {
+                s_h[q] = J.fx[j0 + q];
+                s_l[q] = J.fl[j0 + q];
+                s_x[q] = J.dx[j0 + q];
+                s_n[q] = J.dn[j0 + q];
+            }
+            __syncthreads();
+            uint32_t mask[kTileJ / 32];
+#pragma unroll
+            for (int w = 0; w < kTileJ / 32; ++w) {
+                uint32_t mw = 0u;
+#pragma unroll 8
+                for (int b = 0; b < 32; ++b) {
+                    const int jj = 32 * w + b;
+                    const float4 th = s_h[jj], tl = s_l[jj];
+                    const float fdx = (sh.x - th.x) + (sl.x - tl.x);
+                    const float fdy = (sh.y - th.y) + (sl.y - tl.y);
+                    const float fdz = (sh.z - th.z) + (sl.z - tl.z);
+                    const bool nr = dist2_32(fdx, fdy, fdz) < J.rho2 && th.w != 0.f && j0 + jj != S;
+                    mw |= nr ? (1u << b) : 0u;
+                }
+                mask[w] = mw;
+            }
+#pragma unroll
+            for (int w = 0; w < kTileJ / 32; ++w) {
+                uint32_t mw = mask[w];
+                while (mw) {
+                    const int jj = 32 * w + (__ffs((int)mw) - 1);
+                    mw &= mw - 1u;
+                    const double4 Y = s_x[jj], Nt = s_n[jj];
+                    const double dx = X.x - Y.x, dy = X.y - Y.y, dz = X.z - Y.z;
+                    const double r2 = dx * dx + dy * dy + dz * dz;
+                    const double inv = 1.0 / r2;
+                    const double q = Nn.x * dx + Nn.y * dy + Nn.z * dz;
+                    double K, Kqr;
+                    kg64<GEN>(q, r2, inv, alpha, beta, K, Kqr);
+                    if (!GRAD) {
+                        e += K * Y.w;
+                        continue;
+                    }
+                    const double qp = Nt.x * dx + Nt.y * dy + Nt.z * dz;
+                    double Kp, Kpqr;
+                    kg64<GEN>(qp, r2, inv, alpha, beta, Kp, Kpqr);
+                    const double tt = Y.w * inv;
+                    const double aq = Kqr * tt, ap = Kpqr * tt, KK = K + Kp, cc = KK * tt;
+                    c[0] += aq;
+                    c[1] += ap * Nt.x;
+                    c[2] += ap * Nt.y;
+                    c[3] += ap * Nt.z;
+                    c[4] += cc * dx;
+                    c[5] += cc * dy;
+                    c[6] += cc * dz;
+                    c[7] += aq * dx;
+                    c[8] += aq * dy;
+                    c[9] += aq * dz;
+                    c[10] += KK * Y.w;
+                }
+            }
+        }
+    }
+    if (S >= J.irows) return;
+    if (!GRAD) {
+        J.part[S] = e;
+        return;
+    }
+    const double aS = X.w;
+    double o[7];
+    o[0] = aS * (alpha * (Nn.x * c[0] + c[1]) - beta * c[4]);
+    o[1] = aS * (alpha * (Nn.y * c[0] + c[2]) - beta * c[5]);
+    o[2] = aS * (alpha * (Nn.z * c[0] + c[3]) - beta * c[6]);
+    o[3] = aS * alpha * c[7];
+    o[4] = aS * alpha * c[8];
+    o[5] = aS * alpha * c[9];
+    o[6] = c[10];
+#pragma unroll
+    for (int m = 0; m < 7; ++m) J.part[m * J.irows + S] = o[m];
+}
+
 // ============================================================== split reduction
 
 __global__ void k_reduce_splits(const double* __restrict__ part, int n_split, int nacc,
@@ -850,7 +1031,7 @@ PairPlan plan_for(int kind, int precision, int k, int64_t nF, int64_t cap)
 PairJob make_pair_job(const FaceData& fd, const PairPlan& pl, double* part, const void* ub)
 {
     PairJob J;
-    J.fx = fd.fx; J.fl = fd.fl; J.fn = fd.fn; J.dx = fd.dx; J.dn = fd.dn;
+    J.fx = fd.fx; J.fl = fd.fl; J.fn = fd.fn; J.dx = fd.dx; J.dn = fd.dn; J.tbox = fd.tbox;
     J.ub = ub;
     J.part = part;
     J.irows = pl.irows;
@@ -963,6 +1144,23 @@ static hipError_t launch_frac_k(const PairJob* jobs, int njobs, int precision, d
             hipLaunchKernelGGL((k_frac32<kNiFrac32, KC, true>), grid, block, 0, s, jb, (float)expo);
         else
             hipLaunchKernelGGL((k_frac32<kNiFrac32, KC, false>), grid, block, 0, s, jb, (float)expo);
+    });
+}
+
+int near_block_faces() { return kNearI; }
+
+hipError_t launch_near64(const PairJob* jobs, int njobs, double alpha, double beta, bool grad, hipStream_t s)
+{
+    const dim3 block(kNearI);
+    const bool gen = !is_p6(alpha, beta);
+    return for_each_batch(jobs, njobs, [&](const PairBatch& jb, dim3 grid) {
+        if (grad) {
+            if (gen) hipLaunchKernelGGL((k_near64<true, true>), grid, block, 0, s, jb, alpha, beta);
+            else hipLaunchKernelGGL((k_near64<false, true>), grid, block, 0, s, jb, alpha, beta);
+        } else {
+            if (gen) hipLaunchKernelGGL((k_near64<true, false>), grid, block, 0, s, jb, alpha, beta);
+            else hipLaunchKernelGGL((k_near64<false, false>), grid, block, 0, s, jb, alpha, beta);
+        }
     });
 }
 
