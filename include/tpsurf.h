@@ -64,14 +64,14 @@ typedef enum {
 /* Arithmetic of the all-pairs sums.  Accumulation is always FP64 per face. */
 typedef enum {
     TP_PREC_FP32_HILO = 0,  /* FP32 pair terms; barycenter differences from hi+lo FP32
-                               splits of the FP64 barycenters (default)                   */
+                               splits of the FP64 barycenters                             */
     TP_PREC_FP32 = 1,       /* FP32 pair terms from FP32-rounded barycenters              */
     TP_PREC_FP64 = 2,       /* FP64 pair terms                                            */
     TP_PREC_FP32_NEAR64 = 3 /* as TP_PREC_FP32_HILO for the energy and its differential,
                                except that pairs whose barycenters are closer than twice
                                the mean edge length of the problem's first mesh (tested on
                                the FP32 hi+lo distance) are summed in FP64; the fractional
-                               apply is as TP_PREC_FP32_HILO                               */
+                               apply is as TP_PREC_FP32_HILO (default)                     */
 } tp_precision;
 
 typedef struct {
@@ -80,7 +80,7 @@ typedef struct {
     double sigma;        /* order parameter of L^sigma; < 0 selects 2 - s with
                             s = (beta - 2)/alpha (= 2 - 2/p when beta = 2 alpha,
                             Sec. 2.3 and Sec. 5.2); default -1 -> 1/3 at p = 6           */
-    int    precision;    /* tp_precision, default TP_PREC_FP32_HILO                      */
+    int    precision;    /* tp_precision, default TP_PREC_FP32_NEAR64                    */
     double cg_rtol;      /* CG stops when ||b - C x|| <= cg_rtol ||b||, default 1e-10   */
     int    cg_maxiter;   /* default 20000                                               */
     int    cg_precond;   /* 1: two-level additive Schwarz preconditioner (default, used

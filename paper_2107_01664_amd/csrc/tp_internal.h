@@ -340,10 +340,15 @@ __device__ __forceinline__ double wave_sum(double v)
 // advances the generation word that everybody waits on.
 __device__ __forceinline__ bool group_barrier(unsigned* gbar, int w, int W, int* flags)
 {
-    // Every wave's stores are complete before the workgroup barrier; thread 0's agent-scope
-    // acquire-release arrival then publishes them and the acquire fence after the wait
-    // makes the other workgroups' stores visible to the whole workgroup.
+    // The workgroup barrier alone does not wait for global stores (it only orders them for
+    // waves of the same CU), and a release by thread 0 waits for its own wave's stores only.
+    // So every wave first waits until its own stores have been acknowledged by L2
+    // (s_waitcnt vmcnt(0), immediate 0x0F70: expcnt and lgkmcnt at their maxima); thread 0's
+    // agent-scope release (L2 write-back) then covers the stores of the whole workgroup,
+    // and its acquire fence after the wait makes the other workgroups' stores visible to the
+    // whole workgroup (the caches it invalidates are shared by the workgroup's waves).
     __shared__ int ok_sh;
+    __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;

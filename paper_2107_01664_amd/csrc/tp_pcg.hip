@@ -11,21 +11,22 @@
 // term (d / m) 1 1^T per component (d a diagonal scale, m its size), which leaves the action
 // on per-component mean-zero vectors equal to the pseudo-inverse.
 //
-// The solver is the pipelined form of preconditioned CG (Ghysels and Vanroose 2014): with
-// u = M^{-1} r and w = C u, the sums gamma = (r,u), delta = (w,u) and (r,r) of iteration i
-// are reduced in the same grid exchange that applies the preconditioner and the matrix to
-// w_i (m = M^{-1} w_i, n = C m), and the auxiliary recurrences z = n + beta z, q = m + beta q,
-// s = w + beta s, p = u + beta p, x += alpha p, r -= alpha s, u -= alpha q, w -= alpha z
-// carry the rest.  One workgroup of kBS threads owns one block (one row per thread) and
-// keeps its C_BB^{-1} in LDS for the whole solve.  Each iteration has ONE grid exchange
-// (two-level counter barrier, bounded spin): before it, every block publishes its block
-// solve v = C_BB^{-1} w_B, the block sums of w (coarse right-hand side) and its partial
-// sums; after it, every block forms the coarse values of its own and neighbouring blocks,
-// m = v + c(block) and C m from the neighbours' v.  All partial sums are added in block
-// order by every workgroup, so every workgroup takes the same decisions and the result does
-// not depend on scheduling.  The recursive residual drifts from b - C x in the pipelined
-// recurrences; every solve therefore ends by checking the true residual and restarts from
-// it when it has not reached the tolerance.
+// The solver is the Chronopoulos-Gear form of preconditioned CG: with u = M^{-1} r and
+// w = C u, the sums gamma = (r,u) and delta = (w,u) give beta = gamma / gamma_old and
+// alpha = gamma / (delta - beta gamma / alpha_old), and p = u + beta p, s = w + beta s (= C p),
+// x += alpha p, r -= alpha s.  One workgroup of kBS threads owns one block (one row per
+// thread) and keeps its C_BB^{-1} in LDS for the whole solve.  An iteration has two grid
+// exchanges (two-level counter barrier, bounded spin).  In the first, every block publishes
+// its block solve v = C_BB^{-1} r_B and the block sums of r (coarse right-hand side); after
+// it, every block forms the coarse values of its own and neighbouring blocks, u = v + c(block)
+// and C u from the neighbours' v.  In the second, the block partials of (r,u), (w,u) and
+// (r,r) are added.  All partial sums are added in block order by every workgroup, so every
+// workgroup takes the same decisions and the result does not depend on scheduling.  (The
+// pipelined form, which folds the sums into the next exchange, lost convergence here:
+// relative perturbations of 1e-15 per iteration in its auxiliary recurrences already cost
+// 15 % more iterations and 1e-13 stalled it, while this form is unchanged up to 1e-13.)
+// Every solve ends by checking the true residual b - C x and restarts from it when the
+// recursively updated residual has drifted.
 #include "tp_internal.h"
 
 #include <algorithm>
@@ -264,8 +265,8 @@ struct PcgShared {
     double r[kBS * KG];
     double rho[kMaxNbPcg * KG];
     double c[kMaxNbn * KG];
-    double wave[2 * 4 * KG];
-    double sums[4 * KG];
+    double wave[2 * 3 * KG];
+    double sums[3 * KG];
     double part[kBS];
     int32_t nbl[kMaxNbn];
 };
@@ -377,15 +378,14 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
         __syncthreads();
     };
 
-    double x[KG], r[KG], u[KG], w[KG], p[KG], s[KG], q[KG], z[KG];
+    double x[KG], r[KG], p[KG], s[KG];
     double m[KG], an[KG];
 
-    // One exchange round for the vector y (own rows): before the barrier, v = C_BB^{-1} y_B,
-    // the block sums of y (coarse right-hand side) and, with dots, the block partials of
-    // (r,u), (w,u), (r,r) are published; after it, m = M^{-1} y and an = C M^{-1} y at the
-    // own rows (u = v + c, with the coarse values c of the own and neighbouring blocks), and
-    // with dots S.sums holds the three sums over all blocks.
-    auto round = [&](const double (&y)[KG], bool dots) -> bool {
+    // One exchange for the vector y (own rows): before the barrier, v = C_BB^{-1} y_B and the
+    // block sums of y (coarse right-hand side) are published; after it, m = M^{-1} y and
+    // an = C M^{-1} y at the own rows (m = v + c, with the coarse values c of the own and
+    // neighbouring blocks).
+    auto round = [&](const double (&y)[KG]) -> bool {
         const int cp = pub();
 #pragma unroll
         for (int c = 0; c < KG; ++c) S.r[t * KG + c] = (act && c < k) ? y[c] : 0.0;
@@ -401,25 +401,15 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
 #pragma unroll
             for (int c = 0; c < KG; ++c) v[c] += bij * S.r[j * KG + c];
         }
-        double tmp[4 * KG];
+        double tmp[KG];
 #pragma unroll
-        for (int c = 0; c < KG; ++c) {
-            const bool on = act && c < k;
-            tmp[c] = on ? y[c] : 0.0;
-            tmp[KG + c] = (on && dots) ? r[c] * u[c] : 0.0;
-            tmp[2 * KG + c] = (on && dots) ? w[c] * u[c] : 0.0;
-            tmp[3 * KG + c] = (on && dots) ? r[c] * r[c] : 0.0;
-        }
-        wg_reduce<4 * KG>(tmp, S.wave, S.sums);
+        for (int c = 0; c < KG; ++c) tmp[c] = (act && c < k) ? y[c] : 0.0;
+        wg_reduce<KG>(tmp, S.wave, S.sums);
         if (act)
 #pragma unroll
             for (int c = 0; c < KG; ++c)
                 if (c < k) vbuf(cp)[i * k + c] = v[c];
         if (t < KG && t < k) rhob(cp)[(int64_t)B * k + t] = S.sums[t];
-        if (dots && t < 3 * KG) {
-            const int g = t / KG, c = t - g * KG;
-            if (c < k) redb(cp)[(int64_t)B * 3 * k + g * k + c] = S.sums[KG + t];
-        }
         if (!sync()) return false;
         const double* Vb = vbuf(cp);
         const double* rho = rhob(cp);
@@ -479,7 +469,28 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
         }
 #pragma unroll
         for (int c = 0; c < KG; ++c) an[c] = acc[c];
-        if (dots) grid_sum(std::integral_constant<int, 3 * KG>{}, cp);
+        return true;
+    };
+
+    // Second exchange of an iteration: S.sums = (r,m), (an,m), (r,r) per column, each added
+    // over the blocks in block order.
+    auto dots = [&]() -> bool {
+        double tmp[3 * KG];
+#pragma unroll
+        for (int c = 0; c < KG; ++c) {
+            const bool on = act && c < k;
+            tmp[c] = on ? r[c] * m[c] : 0.0;
+            tmp[KG + c] = on ? an[c] * m[c] : 0.0;
+            tmp[2 * KG + c] = on ? r[c] * r[c] : 0.0;
+        }
+        wg_reduce<3 * KG>(tmp, S.wave, S.sums);
+        const int cp = pub();
+        if (t < 3 * KG) {
+            const int g = t / KG, c = t - g * KG;
+            if (c < k) redb(cp)[(int64_t)B * 3 * k + g * k + c] = S.sums[t];
+        }
+        if (!sync()) return false;
+        grid_sum(std::integral_constant<int, 3 * KG>{}, cp);
         return true;
     };
 
@@ -540,19 +551,13 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
     constexpr int kMaxRestarts = 6;
     bool have_bb = false;
     for (int cycle = 0; cycle <= kMaxRestarts; ++cycle) {
-        // ---- start of a cycle from the current (true) residual r: u = M^{-1} r, w = C u
-        if (!round(r, false)) return;
+        // ---- a cycle starts from the current (true) residual r
 #pragma unroll
-        for (int c = 0; c < KG; ++c) {
-            u[c] = m[c];
-            w[c] = an[c];
-            p[c] = s[c] = q[c] = z[c] = 0.0;
-        }
+        for (int c = 0; c < KG; ++c) p[c] = s[c] = 0.0;
         bool first = true;
-        // ---- iterations (pipelined: the sums of iteration i are reduced in the same
-        //      exchange as M^{-1} w_i and C M^{-1} w_i)
         for (;;) {
-            if (!round(w, true)) return;
+            if (!round(r)) return;           // m = M^{-1} r, an = C m
+            if (!dots()) return;             // (r,m), (an,m), (r,r)
             bool conv = true;
             const bool can = total_it < A.maxiter;
 #pragma unroll
@@ -576,15 +581,11 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
                     gam[c] = g;
                     alpha[c] = al;
                 }
-                // columns that converged (or are done) keep al = be = 0: x, r, u, w stay
-                z[c] = an[c] + be * z[c];
-                q[c] = m[c] + be * q[c];
-                s[c] = w[c] + be * s[c];
-                p[c] = u[c] + be * p[c];
+                // columns that converged (or are done) keep al = 0: x and r stay
+                p[c] = m[c] + be * p[c];
+                s[c] = an[c] + be * s[c];
                 x[c] += al * p[c];
                 r[c] -= al * s[c];
-                u[c] -= al * q[c];
-                w[c] -= al * z[c];
             }
             have_bb = true;
             __syncthreads();
