@@ -271,6 +271,40 @@ struct PcgShared {
     int32_t nbl[kMaxNbn];
 };
 
+// Sum of n values p[0], p[stride], ... in a fixed order: four interleaved partial sums, so
+// four loads are in flight at a time, added as (s0 + s1) + (s2 + s3).
+__device__ __forceinline__ double sum_fixed(const double* __restrict__ p, int n, int64_t stride)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {
+        const double v0 = p[(int64_t)i * stride], v1 = p[(int64_t)(i + 1) * stride];
+        const double v2 = p[(int64_t)(i + 2) * stride], v3 = p[(int64_t)(i + 3) * stride];
+        a0 += v0;
+        a1 += v1;
+        a2 += v2;
+        a3 += v3;
+    }
+    for (; i < n; ++i) a0 += p[(int64_t)i * stride];
+    return (a0 + a1) + (a2 + a3);
+}
+
+// Dot product sum_i a[i] b[i * bstride] in the same fixed order.
+__device__ __forceinline__ double dot_fixed(const double* __restrict__ a, const double* __restrict__ b, int n,
+                                            int bstride)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {
+        a0 += a[i] * b[i * bstride];
+        a1 += a[i + 1] * b[(i + 1) * bstride];
+        a2 += a[i + 2] * b[(i + 2) * bstride];
+        a3 += a[i + 3] * b[(i + 3) * bstride];
+    }
+    for (; i < n; ++i) a0 += a[i] * b[i * bstride];
+    return (a0 + a1) + (a2 + a3);
+}
+
 // Fixed-order workgroup reduction of M values per thread (kBS = 128 threads, two waves):
 // butterfly within each wave, then wave 0 + wave 1.  Result in out[0 .. M).
 template <int M>
@@ -365,16 +399,12 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
             double acc = 0.0;
             if (cc < k) {
                 const int b0 = part * chunk, b1 = min(nb, b0 + chunk);
-                for (int bb = b0; bb < b1; ++bb) acc += red[(int64_t)bb * 3 * k + g * k + cc];
+                if (b1 > b0) acc = sum_fixed(red + (int64_t)b0 * 3 * k + g * k + cc, b1 - b0, 3 * k);
             }
             S.part[q * P + part] = acc;
         }
         __syncthreads();
-        if (t < M) {
-            double acc = 0.0;
-            for (int pp = 0; pp < P; ++pp) acc += S.part[t * P + pp];
-            S.sums[t] = acc;
-        }
+        if (t < M) S.sums[t] = sum_fixed(S.part + t * P, P, 1);
         __syncthreads();
     };
 
@@ -395,11 +425,20 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
         for (int c = 0; c < KG; ++c) v[c] = 0.0;
         // padding rows of the block hold y = 0 and an identity block in C_BB^{-1}, so the
         // product runs over all kBS rows with a fixed trip count
-#pragma unroll 8
-        for (int j = 0; j < kBS; ++j) {
-            const double bij = (double)S.Binv[j * kBS + t];
+        // chunks of CH rows: all LDS loads of a chunk are issued before its FMAs
+        constexpr int CH = KG <= 3 ? 8 : (KG <= 6 ? 4 : 2);
+#pragma unroll 1
+        for (int j0 = 0; j0 < kBS; j0 += CH) {
+            float bj[CH];
+            double yj[CH * KG];
 #pragma unroll
-            for (int c = 0; c < KG; ++c) v[c] += bij * S.r[j * KG + c];
+            for (int q = 0; q < CH; ++q) bj[q] = S.Binv[(j0 + q) * kBS + t];
+#pragma unroll
+            for (int q = 0; q < CH * KG; ++q) yj[q] = S.r[j0 * KG + q];
+#pragma unroll
+            for (int q = 0; q < CH; ++q)
+#pragma unroll
+                for (int c = 0; c < KG; ++c) v[c] += (double)bj[q] * yj[q * KG + c];
         }
         double tmp[KG];
 #pragma unroll
@@ -413,9 +452,17 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
         if (!sync()) return false;
         const double* Vb = vbuf(cp);
         const double* rho = rhob(cp);
-        for (int qq = t; qq < nb * KG; qq += kBS) {
-            const int bb = qq / KG, c = qq - bb * KG;
-            S.rho[qq] = c < k ? rho[(int64_t)bb * k + c] : 0.0;
+        // block sums of every block: four loads in flight per thread
+        for (int q0 = t; q0 < nb * KG; q0 += 4 * kBS) {
+            double vv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int qq = q0 + u * kBS, bb = qq / KG, c = qq - bb * KG;
+                vv[u] = (qq < nb * KG && c < k) ? rho[(int64_t)bb * k + c] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (q0 + u * kBS < nb * KG) S.rho[q0 + u * kBS] = vv[u];
         }
         __syncthreads();
         // coarse values c(sl) = sum_bb C0inv[nbl[sl]][bb] rho[bb] for the nbn x KG jobs: each
@@ -430,16 +477,10 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
                 const int job = j0 + jl, sl = job / KG, c = job - sl * KG;
                 const double* row = crow_lds ? S.crow + sl * nb : A.C0inv + (int64_t)S.nbl[sl] * nb;
                 const int b0 = part * chunk, b1 = min(nb, b0 + chunk);
-                double acc = 0.0;
-                for (int bb = b0; bb < b1; ++bb) acc += row[bb] * S.rho[bb * KG + c];
-                S.part[jl * P + part] = acc;
+                S.part[jl * P + part] = b1 > b0 ? dot_fixed(row + b0, S.rho + b0 * KG + c, b1 - b0, KG) : 0.0;
             }
             __syncthreads();
-            if (t < nj) {
-                double acc = 0.0;
-                for (int pp = 0; pp < P; ++pp) acc += S.part[t * P + pp];
-                S.c[j0 + t] = acc;
-            }
+            if (t < nj) S.c[j0 + t] = sum_fixed(S.part + t * P, P, 1);
             __syncthreads();
         }
         double acc[KG];
@@ -533,6 +574,7 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
         return true;
     };
 
+    const double rtol2 = A.rtol * A.rtol;
     double bb[KG], rr[KG], gam[KG], alpha[KG];
     bool done[KG];
     int its[KG];
@@ -569,7 +611,7 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
                     done[c] = (c >= k) || !(bb[c] > 0.0);
                 }
                 double al = 0.0, be = 0.0;
-                if (!done[c] && sqrt(rr[c] / bb[c]) > A.rtol) {
+                if (!done[c] && rr[c] > rtol2 * bb[c]) {
                     conv = false;
                     if (!can) {
                     } else if (first) {
@@ -593,7 +635,7 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
             ++total_it;
 #pragma unroll
             for (int c = 0; c < KG; ++c)
-                if (!done[c] && sqrt(rr[c] / bb[c]) > A.rtol) its[c] = total_it;
+                if (!done[c] && rr[c] > rtol2 * bb[c]) its[c] = total_it;
             first = false;
         }
         // ---- verify: recompute the true residual, restart from it if needed
@@ -603,7 +645,7 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
         for (int c = 0; c < KG; ++c) {
             if (!done[c]) {
                 rr[c] = S.sums[c];
-                if (sqrt(rr[c] / bb[c]) <= A.rtol) done[c] = true;
+                if (rr[c] <= rtol2 * bb[c]) done[c] = true;
             }
             all = all && done[c];
         }

@@ -351,3 +351,23 @@ def test_poisson_true_residual_torus40k(tp, torus40k, pc):
     r = np.linalg.norm(Pb - C @ x, axis=0) / np.linalg.norm(Pb, axis=0)
     assert r.max() <= 2e-10, r
     assert np.abs(O.project_mean_zero(x, labels) - x).max() <= 1e-12 * np.abs(x).max()
+
+
+def test_pcg_columns_together_like_alone(tp, torus40k):
+    """The columns of one solve are independent systems: solved together (k = 9) they take
+    about as many iterations as the slowest one solved alone.  The right-hand sides are
+    those of the preconditioner's second solve (L^sigma of a first solution), on which an
+    iteration that amplifies rounding (the pipelined form) needed ten times more."""
+    m = torus40k
+    b = mg.random_columns(m.nV, 9, 2)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        x1, _ = P.poisson_solve(dev(b))
+        Lx = P.fractional_apply(x1)
+        alone = [P.poisson_solve(Lx[:, c:c + 1].contiguous())[1].cg_iters[0] for c in range(9)]
+        x9, rep = P.poisson_solve(Lx.contiguous())
+        for c in range(9):
+            xc, _ = P.poisson_solve(Lx[:, c:c + 1].contiguous())
+            assert rel(x9[:, c].cpu().numpy(), xc[:, 0].cpu().numpy()) <= 1e-8
+    print(f"[pcg] torus40k second-solve right-hand sides: alone {alone}, together {rep.cg_iters[0]}", flush=True)
+    assert rep.cg_relres[0] <= 1e-10
+    assert rep.cg_iters[0] <= max(alone) + 5
