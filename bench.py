@@ -12,6 +12,8 @@ Prints ONE JSON line (rank 0).  `--gpus N` with N > 1 exits: the path runs on on
 
 `--copy-probe` instead runs a plain device-to-device copy of known size; its FETCH_SIZE
 and WRITE_SIZE counter readings calibrate those counters for the traffic figure.
+`--pairs-only` runs only the all-pairs launches of the step (E + dE and L^sigma u) and
+prints their timings: a short program for hardware-counter passes.
 """
 from __future__ import annotations
 
@@ -31,6 +33,31 @@ FLOP_PER_PAIR_GRAD = 57.0
 FLOP_PER_PAIR_ENERGY = 21.0
 PEAK_FP32_VALU_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+
+# HBM bytes per launch of the E + dE kernel on this workload, from one FETCH_SIZE and one
+# WRITE_SIZE counter pass (`--pairs-only`), each scaled by what the same counter reads for
+# a plain copy of known size (FETCH_SIZE x 2.00, WRITE_SIZE x 1.00).  Reported only while
+# the kernel's sources are the ones the passes measured.
+GRAD_TRAFFIC = {
+    "sources": ["paper_2107_01664_amd/csrc/tp_pairs.hip", "paper_2107_01664_amd/csrc/tp_internal.h"],
+    "sha256": "1c1f2dc41d45fc1bcbfa2059e586784bf08b67bac54bc2497c4bcc9b84ac8b28",
+    "fetch_bytes": 55862 * 1024 * 2,
+    "write_bytes": 64148 * 1024,
+}
+
+
+def grad_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    try:
+        for f in GRAD_TRAFFIC["sources"]:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+    except OSError:
+        return None
+    if h.hexdigest() != GRAD_TRAFFIC["sha256"]:
+        return None
+    return GRAD_TRAFFIC["fetch_bytes"] + GRAD_TRAFFIC["write_bytes"]
 
 
 def frac_flop_per_pair(k: float) -> float:
@@ -54,6 +81,8 @@ def parse():
                     help="run only the serving comparison and print its JSON line")
     ap.add_argument("--sweep", action="store_true",
                     help="precision and Barnes-Hut sweep (bumpy sphere, linked tori) instead of the step")
+    ap.add_argument("--pairs-only", action="store_true",
+                    help="time only the all-pairs launches of the step (for counter passes)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 256 MiB device copy 5 times (counter calibration)")
     return ap.parse_args()
@@ -302,6 +331,26 @@ def main():
         _, rep = P.precond_apply(dE, out=x)
         return E, rep
 
+    if a.pairs_only:
+        for _ in range(a.warmup):
+            P.gradient(out=dE)
+            P.fractional_apply(u, out=Lu)
+        torch.cuda.synchronize()
+        tp.profile_reset()
+        tp.profile_enable(True)
+        for _ in range(a.steps):
+            P.gradient(out=dE)
+            P.fractional_apply(u, out=Lu)
+        torch.cuda.synchronize()
+        tp.profile_enable(False)
+        g, f = tp.profile_get(tp.KIND_GRAD), tp.profile_get(tp.KIND_FRAC)
+        print(json.dumps({"pairs_only": True, "faces": nF, "grad_launches": g["launches"],
+                          "grad_avg_ms": g["ms_total"] / max(1, g["launches"]),
+                          "frac_launches": f["launches"], "frac_avg_ms": f["ms_total"] / max(1, f["launches"])}),
+              flush=True)
+        P.close()
+        return
+
     for _ in range(a.warmup):
         step()
     torch.cuda.synchronize()
@@ -364,7 +413,8 @@ def main():
             "peak": PEAK_FP32_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": grad_tflops / PEAK_FP32_VALU_TFLOPS,
-            "traffic": None,
+            "traffic": grad_traffic(),
+            "traffic_unit": "HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "flop_per_pair": FLOP_PER_PAIR_GRAD,
             "avg_launch_ms": grad_ms,
             "launches": g["launches"],
