@@ -261,6 +261,16 @@ struct tp_problem {
     uint64_t bh_ver = ~0ull;         // geometry version the tree was built for
     double rho2 = 0.0;               // FP64 near-field radius^2: (2 x mean edge of the first mesh)^2
 
+    // FP64 near-field grid (TP_PREC_FP32_NEAR64), rebuilt per geometry
+    DevBuf<uint32_t> ng_kin, ng_kout;
+    DevBuf<int32_t> ng_vin, ng_vout;
+    DevBuf<float4> ng_sfx, ng_sfl;
+    DevBuf<int2> ng_cell;
+    DevBuf<char> ng_tmp;
+    DevBuf<NearGridParams> ng_prm;
+    NearGrid ng;
+    uint64_t ng_ver = ~0ull;         // geometry version the grid was built for
+
     // pinned host mirrors of device scalars, flags and CG results; multi-problem CG tables
     HostBuf<double> hs, hrelres;
     HostBuf<int> hflags, hiters;
@@ -288,6 +298,8 @@ struct tp_problem {
              bh_nX.bytes() + bh_nlo.bytes() + bh_nhi.bytes() + bh_nr2.bytes() + bh_gS.bytes() + bh_eS.bytes() +
              bh_accF.bytes() + bh_accN.bytes() + bh_kin.bytes() + bh_kout.bytes() + bh_tmp.bytes() +
              bh_order.bytes() + bh_pos.bytes() + bh_counts.bytes();
+        b += ng_kin.bytes() + ng_kout.bytes() + ng_vin.bytes() + ng_vout.bytes() + ng_sfx.bytes() + ng_sfl.bytes() +
+             ng_cell.bytes() + ng_tmp.bytes() + ng_prm.bytes();
         return b;
     }
 };
@@ -796,6 +808,44 @@ double gradient_energy(const tp_problem* P, double v)
 
 bool near_field(const tp_problem* P) { return P->prm.precision == TP_PREC_FP32_NEAR64; }
 
+// Device bytes of the near-field grid of a problem of nF faces.
+size_t near_grid_bytes(int64_t nF)
+{
+    const int64_t gm = near_grid_gmax(nF);
+    return (size_t)nF * (4 + 4 + 4 + 4 + 16 + 16) + (size_t)(gm * gm * gm) * sizeof(int2) +
+           near_grid_sort_temp_bytes(nF) + sizeof(NearGridParams);
+}
+
+// The near-field grid of the current face data (built once per geometry).
+tp_status ensure_near_grid(tp_problem* P)
+{
+    hipStream_t s = P->stream;
+    const size_t n = (size_t)P->nF;
+    NearGrid& g = P->ng;
+    if (!g.prm) {
+        g.gmax = near_grid_gmax(P->nF);
+        const size_t gm = (size_t)g.gmax;
+        TP_TRY(P->ng_kin.ensure(n, s));
+        TP_TRY(P->ng_kout.ensure(n, s));
+        TP_TRY(P->ng_vin.ensure(n, s));
+        TP_TRY(P->ng_vout.ensure(n, s));
+        TP_TRY(P->ng_sfx.ensure(n, s));
+        TP_TRY(P->ng_sfl.ensure(n, s));
+        TP_TRY(P->ng_cell.ensure(gm * gm * gm, s));
+        g.sort_bytes = near_grid_sort_temp_bytes(P->nF);
+        TP_TRY(P->ng_tmp.ensure(g.sort_bytes, s));
+        TP_TRY(P->ng_prm.ensure(1, s));
+        g.kin = P->ng_kin.p; g.kout = P->ng_kout.p; g.vin = P->ng_vin.p; g.vout = P->ng_vout.p;
+        g.sfx = P->ng_sfx.p; g.sfl = P->ng_sfl.p; g.cell = P->ng_cell.p; g.sort_tmp = P->ng_tmp.p;
+        g.prm = P->ng_prm.p;
+    }
+    if (P->ng_ver != P->geom_ver) {
+        TP_HIP(launch_near_grid_build(g, P->fd, P->nF, (float)P->rho2, s));
+        P->ng_ver = P->geom_ver;
+    }
+    return TP_OK;
+}
+
 // The FP64 near-field slice (index n_split of the partial buffer, nacc accumulators) of
 // every problem of the batch that uses it, in one launch.
 tp_status enqueue_near(const Batch& B, const std::vector<PairPlan>& plans, int nacc, bool grad)
@@ -805,10 +855,16 @@ tp_status enqueue_near(const Batch& B, const std::vector<PairPlan>& plans, int n
         tp_problem* P = B[m];
         if (!near_field(P)) continue;
         const PairPlan& pl = plans[m];
+        TP_TRY(ensure_near_grid(P));
         PairJob J = make_pair_job(P->fd, pl, P->part.p + (size_t)pl.n_split * nacc * pl.irows);
         J.n_itiles = (int)((P->nF + near_block_faces() - 1) / near_block_faces());
         J.tiles_per_split = J.ntiles_j;
         J.rho2 = (float)P->rho2;
+        J.nord = P->ng.vout;
+        J.nfx = P->ng.sfx;
+        J.nfl = P->ng.sfl;
+        J.ncell = P->ng.cell;
+        J.ngp = P->ng.prm;
         jobs.push_back(J);
     }
     if (jobs.empty()) return TP_OK;
@@ -1696,11 +1752,14 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
     b += 8 * part + 8 * gface + 8.0 * kf * pf.irows + (double)cap * ((kf + 3) / 4 * 4) * esz;
     // step work arrays, per-face volumes and edge lengths, CG tables
     b += 8 * n * ncol * 4 + 8 * n * 3 * 3 + 16 * f + 4096;
-    // Barnes-Hut tree, keys, sort scratch and per-face sums
-    if (prm.theta > 0.0 || prm.precision == TP_PREC_FP32_NEAR64) {
+    // Barnes-Hut tree, keys, sort scratch and per-face sums (allocated at creation, where
+    // the Morton order of the faces is computed with them)
+    {
         const double M = (double)bh_node_count(nF, prm.leaf_size, nullptr);
         b += f * (176.0 + 56.0) + M * 144.0 + (double)bh_sort_temp_bytes(nF) + 64;
     }
+    // FP64 near-field grid
+    if (prm.precision == TP_PREC_FP32_NEAR64) b += (double)near_grid_bytes(nF);
     return (uint64_t)(b * 1.02) + 65536;
 }
 

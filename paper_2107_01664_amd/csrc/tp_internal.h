@@ -91,6 +91,17 @@ hipError_t launch_face_from_quantities(const double* X, const double* N, const d
 int64_t face_capacity(int64_t nF, int ni_max);
 PairPlan plan_pairs(int64_t nF, int64_t cap, int ni, int occupancy_per_cu);
 
+// Uniform cell grid of the FP64 near field (TP_PREC_FP32_NEAR64), built per geometry on
+// the FP32 barycenters (hi parts): g cells per axis on the cube [lo, lo + g / inv_cs)^3,
+// cells at least 1.01 x the near radius wide, so the two faces of a near pair lie in the
+// same or in adjacent cells.
+struct NearGridParams {
+    float lo[3];
+    float inv_cs;     // cells per unit length
+    int g;            // cells per axis
+    int n;            // faces in the grid (the real faces of the problem)
+};
+
 // One problem's share of an all-pairs launch.  A launch covers up to kMaxPairJobs
 // problems of the same precision and exponents; problem m owns the workgroups
 // [block0, block0 + n_itiles * n_split) of a 1-D grid, laid out i-tile fastest.  The
@@ -107,6 +118,13 @@ struct PairJob {
     int n_itiles = 0, tiles_per_split = 0, ntiles_j = 0, block0 = 0;
     float rho2 = 0.f;               // TP_PREC_FP32_NEAR64: pairs with r2 < rho2 are left out
     const float4* tbox = nullptr;   // tile boxes (FaceData::tbox)
+    // near-field grid (NearGrid): faces in cell order, their FP32 hi / lo barycenters in
+    // that order, [begin, end) of every cell, parameters
+    const int32_t* nord = nullptr;
+    const float4* nfx = nullptr;
+    const float4* nfl = nullptr;
+    const int2* ncell = nullptr;
+    const NearGridParams* ngp = nullptr;
 };
 constexpr int kMaxPairJobs = 16;
 PairJob make_pair_job(const FaceData& fd, const PairPlan& pl, double* part, const void* ub = nullptr);
@@ -292,11 +310,30 @@ hipError_t launch_bh_eval(const BhBuffers& b, int64_t nF, int leaf, double theta
                           double beta, const FaceData& fd, bool grad, double* gface, int64_t gstride,
                           hipStream_t s);
 
+// Buffers of the near-field grid of one problem (device memory owned by the problem).
+struct NearGrid {
+    uint32_t* kin = nullptr;      // [nF] cell index of each face
+    uint32_t* kout = nullptr;     // [nF] sorted
+    int32_t* vin = nullptr;       // [nF] face numbers
+    int32_t* vout = nullptr;      // [nF] faces in cell order (ties in face order)
+    float4* sfx = nullptr;        // [nF] fx in cell order
+    float4* sfl = nullptr;        // [nF] fl in cell order
+    int2* cell = nullptr;         // [gmax^3] (begin, end) in cell order; empty cells (0, 0)
+    void* sort_tmp = nullptr;
+    size_t sort_bytes = 0;
+    int gmax = 1;
+    NearGridParams* prm = nullptr;
+};
+int near_grid_gmax(int64_t nF);                 // cells per axis at most: cbrt(8 nF), 1..128
+size_t near_grid_sort_temp_bytes(int64_t nF);
+// Grid of the first nF faces of fd for the squared near radius rho2.
+hipError_t launch_near_grid_build(const NearGrid& g, const FaceData& fd, int64_t nF, float rho2, hipStream_t s);
+
 // FP64 near field (TP_PREC_FP32_NEAR64), as one launch over the problems of a batch: for
 // every face S, the pairs (S, T), T != S, whose FP32 hi+lo squared barycenter distance is
 // below the job's rho2 (exactly the pairs the FP32 kernels leave out), summed in FP64 into
-// the job's partial slice ([7][irows] with grad, else [irows]).  Only j-tiles whose box lies
-// within the near radius of the i-range are visited.
+// the job's partial slice ([7][irows] with grad, else [irows]).  The candidates T of S are
+// the faces of the 27 grid cells around S's cell.
 hipError_t launch_near64(const PairJob* jobs, int njobs, double alpha, double beta, bool grad, hipStream_t s);
 int near_block_faces();           // faces S per near-field workgroup (n_itiles of a near job)
 

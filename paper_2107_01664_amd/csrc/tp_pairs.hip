@@ -17,7 +17,10 @@
 // to the 6th power, and q is small for near pairs on a smooth surface).
 #include "tp_internal.h"
 
+#include <hipcub/hipcub.hpp>
+
 #include <algorithm>
+#include <cmath>
 #include <mutex>
 #include <unordered_map>
 #include <vector>
@@ -743,81 +746,49 @@ __device__ __forceinline__ void kg64(double q, double r2, double inv, double alp
     }
 }
 
-constexpr int kNearChunk = 1024;   // j-tiles tested per pass
-constexpr int kNearI = 64;         // faces S per workgroup (one wave)
+constexpr int kNearBlock = 128;    // faces S per near-field workgroup
 
-// Workgroup = one wave of kNearI faces S.  Candidate j-tiles are tested in chunks by all
-// lanes at once (flags in LDS) and visited in increasing order; in a visited tile every
-// lane first forms its near mask over the kTileJ faces with FP32 arithmetic only, then
-// evaluates its own near pairs in FP64 (in increasing T).
-template <bool GEN, bool GRAD>
-__global__ __launch_bounds__(kNearI) void k_near64(PairBatch jb, double alpha, double beta)
+// Cell of an FP32 barycenter: floor((x - lo) inv_cs) per axis, clamped to [0, g).
+__device__ __forceinline__ int near_cell_axis(float x, float lo, float inv_cs, int g)
 {
-    __shared__ float4 s_h[kTileJ], s_l[kTileJ];
-    __shared__ double4 s_x[kTileJ], s_n[kTileJ];
-    __shared__ unsigned char s_flag[kNearChunk];
+    const int c = (int)floorf((x - lo) * inv_cs);
+    return c < 0 ? 0 : (c >= g ? g - 1 : c);
+}
+
+// Workgroup = kNearBlock consecutive faces of the cell order (lanes of a wave share cells,
+// so their candidate loops run nearly in step).  Face S visits the 27 cells around its own
+// in a fixed order and, in each, the faces in cell order: for every candidate T it forms the
+// FP32 hi+lo squared distance exactly as the FP32 kernels do, and evaluates the pair in
+// FP64 when that distance is below rho2.  The sums of S therefore have a fixed order.
+template <bool GEN, bool GRAD>
+__global__ __launch_bounds__(kNearBlock) void k_near64(PairBatch jb, double alpha, double beta)
+{
     const PairJob J = pick_job(jb);
-    const int64_t ibase = (int64_t)((int)blockIdx.x - J.block0) * kNearI;
-    const int64_t S = ibase + threadIdx.x;
-    const float4 sh = J.fx[S], sl = J.fl[S];
+    const NearGridParams G = *J.ngp;
+    const int i = ((int)blockIdx.x - J.block0) * kNearBlock + (int)threadIdx.x;
+    if (i >= G.n) return;
+    const int S = J.nord[i];
+    const float4 sh = J.nfx[i], sl = J.nfl[i];
     const double4 X = J.dx[S], Nn = J.dn[S];
-    // box of this wave's barycenters (FP32 hi parts of real faces)
-    float4 ilo = make_float4(INFINITY, INFINITY, INFINITY, 0.f), ihi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
-    if (sh.w != 0.f) {
-        ilo = make_float4(sh.x, sh.y, sh.z, 0.f);
-        ihi = ilo;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        ilo.x = fminf(ilo.x, __shfl_xor(ilo.x, off)); ilo.y = fminf(ilo.y, __shfl_xor(ilo.y, off));
-        ilo.z = fminf(ilo.z, __shfl_xor(ilo.z, off)); ihi.x = fmaxf(ihi.x, __shfl_xor(ihi.x, off));
-        ihi.y = fmaxf(ihi.y, __shfl_xor(ihi.y, off)); ihi.z = fmaxf(ihi.z, __shfl_xor(ihi.z, off));
-    }
+    const int cx = near_cell_axis(sh.x, G.lo[0], G.inv_cs, G.g);
+    const int cy = near_cell_axis(sh.y, G.lo[1], G.inv_cs, G.g);
+    const int cz = near_cell_axis(sh.z, G.lo[2], G.inv_cs, G.g);
     double c[11];
 #pragma unroll
     for (int m = 0; m < 11; ++m) c[m] = 0.0;
     double e = 0.0;
-    for (int c0 = 0; c0 < J.ntiles_j; c0 += kNearChunk) {
-        __syncthreads();
-        for (int q = threadIdx.x; q < kNearChunk; q += kNearI) {
-            const int jt = c0 + q;
-            s_flag[q] = (jt < J.ntiles_j && tile_may_be_near(ilo, ihi, J.tbox, jt, J.rho2)) ? 1 : 0;
-        }
-        __syncthreads();
-        const int cend = min(kNearChunk, J.ntiles_j - c0);
-        for (int qt = 0; qt < cend; ++qt) {
-            if (!s_flag[qt]) continue;
-            const int64_t j0 = (int64_t)(c0 + qt) * kTileJ;
-            __syncthreads();
-            for (int q = threadIdx.x; q < kTileJ; q += kNearI) {
-                s_h[q] = J.fx[j0 + q];
-                s_l[q] = J.fl[j0 + q];
-                s_x[q] = J.dx[j0 + q];
-                s_n[q] = J.dn[j0 + q];
-            }
-            __syncthreads();
-            uint32_t mask[kTileJ / 32];
-#pragma unroll
-            for (int w = 0; w < kTileJ / 32; ++w) {
-                uint32_t mw = 0u;
-#pragma unroll 8
-                for (int b = 0; b < 32; ++b) {
-                    const int jj = 32 * w + b;
-                    const float4 th = s_h[jj], tl = s_l[jj];
+    for (int z = max(cz - 1, 0); z <= min(cz + 1, G.g - 1); ++z)
+        for (int y = max(cy - 1, 0); y <= min(cy + 1, G.g - 1); ++y)
+            for (int x = max(cx - 1, 0); x <= min(cx + 1, G.g - 1); ++x) {
+                const int2 be = J.ncell[((int64_t)z * G.g + y) * G.g + x];
+                for (int j = be.x; j < be.y; ++j) {
+                    const float4 th = J.nfx[j], tl = J.nfl[j];
                     const float fdx = (sh.x - th.x) + (sl.x - tl.x);
                     const float fdy = (sh.y - th.y) + (sl.y - tl.y);
                     const float fdz = (sh.z - th.z) + (sl.z - tl.z);
-                    const bool nr = dist2_32(fdx, fdy, fdz) < J.rho2 && th.w != 0.f && j0 + jj != S;
-                    mw |= nr ? (1u << b) : 0u;
-                }
-                mask[w] = mw;
-            }
-#pragma unroll
-            for (int w = 0; w < kTileJ / 32; ++w) {
-                uint32_t mw = mask[w];
-                while (mw) {
-                    const int jj = 32 * w + (__ffs((int)mw) - 1);
-                    mw &= mw - 1u;
-                    const double4 Y = s_x[jj], Nt = s_n[jj];
+                    if (!(dist2_32(fdx, fdy, fdz) < J.rho2) || j == i) continue;
+                    const int T = J.nord[j];
+                    const double4 Y = J.dx[T], Nt = J.dn[T];
                     const double dx = X.x - Y.x, dy = X.y - Y.y, dz = X.z - Y.z;
                     const double r2 = dx * dx + dy * dy + dz * dz;
                     const double inv = 1.0 / r2;
@@ -846,9 +817,6 @@ __global__ __launch_bounds__(kNearI) void k_near64(PairBatch jb, double alpha, d
                     c[10] += KK * Y.w;
                 }
             }
-        }
-    }
-    if (S >= J.irows) return;
     if (!GRAD) {
         J.part[S] = e;
         return;
@@ -864,6 +832,85 @@ __global__ __launch_bounds__(kNearI) void k_near64(PairBatch jb, double alpha, d
     o[6] = c[10];
 #pragma unroll
     for (int m = 0; m < 7; ++m) J.part[m * J.irows + S] = o[m];
+}
+
+// ------------------------------------------------------------------ near-field grid build
+
+// Grid parameters from the tile boxes (one workgroup): the cube around the box of all
+// FP32 barycenters, g = floor(extent / (1.01 near radius)) cells per axis, 1 <= g <= gmax.
+__global__ __launch_bounds__(256) void k_near_grid_params(const float4* __restrict__ tbox, int ntiles, int64_t nF,
+                                                          float rho2, int gmax, NearGridParams* __restrict__ out)
+{
+    __shared__ float sh[6][256];
+    float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int t = threadIdx.x; t < ntiles; t += 256) {
+        const float4 a = tbox[2 * t], b = tbox[2 * t + 1];
+        lo[0] = fminf(lo[0], a.x); lo[1] = fminf(lo[1], a.y); lo[2] = fminf(lo[2], a.z);
+        hi[0] = fmaxf(hi[0], b.x); hi[1] = fmaxf(hi[1], b.y); hi[2] = fmaxf(hi[2], b.z);
+    }
+    for (int m = 0; m < 3; ++m) {
+        sh[m][threadIdx.x] = lo[m];
+        sh[3 + m][threadIdx.x] = hi[m];
+    }
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int m = 0; m < 3; ++m) {
+                sh[m][threadIdx.x] = fminf(sh[m][threadIdx.x], sh[m][threadIdx.x + w]);
+                sh[3 + m][threadIdx.x] = fmaxf(sh[3 + m][threadIdx.x], sh[3 + m][threadIdx.x + w]);
+            }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        NearGridParams P;
+        float ext = 0.f;
+        for (int m = 0; m < 3; ++m) {
+            P.lo[m] = sh[m][0];
+            ext = fmaxf(ext, sh[3 + m][0] - sh[m][0]);
+        }
+        const float r = 1.01f * sqrtf(rho2);
+        int g = (r > 0.f && ext > 0.f) ? (int)fminf((float)gmax, floorf(ext / r)) : 1;
+        g = g < 1 ? 1 : g;
+        P.g = g;
+        P.inv_cs = ext > 0.f ? (float)g / ext : 0.f;
+        P.n = (int)nF;
+        *out = P;
+    }
+}
+
+__global__ void k_near_grid_keys(const float4* __restrict__ fx, int64_t nF, const NearGridParams* __restrict__ prm,
+                                 uint32_t* __restrict__ key, int32_t* __restrict__ val)
+{
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nF) return;
+    const NearGridParams G = *prm;
+    const float4 p = fx[s];
+    const int cx = near_cell_axis(p.x, G.lo[0], G.inv_cs, G.g);
+    const int cy = near_cell_axis(p.y, G.lo[1], G.inv_cs, G.g);
+    const int cz = near_cell_axis(p.z, G.lo[2], G.inv_cs, G.g);
+    key[s] = (uint32_t)(((int64_t)cz * G.g + cy) * G.g + cx);
+    val[s] = (int32_t)s;
+}
+
+__global__ void k_near_grid_clear(int2* __restrict__ cell, int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) cell[t] = make_int2(0, 0);
+}
+
+// Cell ranges and the face records in cell order.
+__global__ void k_near_grid_mark(const uint32_t* __restrict__ key, const int32_t* __restrict__ val, int64_t nF,
+                                 const float4* __restrict__ fx, const float4* __restrict__ fl, int2* __restrict__ cell,
+                                 float4* __restrict__ sfx, float4* __restrict__ sfl)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nF) return;
+    const uint32_t k = key[i];
+    if (i == 0 || key[i - 1] != k) cell[k].x = (int)i;
+    if (i == nF - 1 || key[i + 1] != k) cell[k].y = (int)(i + 1);
+    const int32_t s = val[i];
+    sfx[i] = fx[s];
+    sfl[i] = fl[s];
 }
 
 // ============================================================== split reduction
@@ -1147,11 +1194,56 @@ static hipError_t launch_frac_k(const PairJob* jobs, int njobs, int precision, d
     });
 }
 
-int near_block_faces() { return kNearI; }
+int near_block_faces() { return kNearBlock; }
+
+int near_grid_gmax(int64_t nF)
+{
+    int g = (int)std::floor(std::cbrt(8.0 * (double)std::max<int64_t>(nF, 1)));
+    return std::max(1, std::min(128, g));
+}
+
+static int near_key_bits(int gmax)
+{
+    const int64_t cells = (int64_t)gmax * gmax * gmax;
+    int b = 1;
+    while (((int64_t)1 << b) < cells) ++b;
+    return b;
+}
+
+size_t near_grid_sort_temp_bytes(int64_t nF)
+{
+    size_t bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                             (const int32_t*)nullptr, (int32_t*)nullptr, (int)std::max<int64_t>(nF, 1),
+                                             0, near_key_bits(near_grid_gmax(nF)));
+    return bytes;
+}
+
+hipError_t launch_near_grid_build(const NearGrid& g, const FaceData& fd, int64_t nF, float rho2, hipStream_t s)
+{
+    if (nF < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_near_grid_params, dim3(1), dim3(256), 0, s, fd.tbox, (int)(fd.cap / kTileJ), nF, rho2,
+                       g.gmax, g.prm);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const unsigned nb = (unsigned)((nF + 255) / 256);
+    hipLaunchKernelGGL(k_near_grid_keys, dim3(nb), dim3(256), 0, s, fd.fx, nF, g.prm, g.kin, g.vin);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    size_t bytes = g.sort_bytes;
+    e = hipcub::DeviceRadixSort::SortPairs(g.sort_tmp, bytes, g.kin, g.kout, g.vin, g.vout, (int)nF, 0,
+                                           near_key_bits(g.gmax), s);
+    if (e != hipSuccess) return e;
+    const int64_t ncell = (int64_t)g.gmax * g.gmax * g.gmax;
+    hipLaunchKernelGGL(k_near_grid_clear, dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, g.cell, ncell);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_near_grid_mark, dim3(nb), dim3(256), 0, s, g.kout, g.vout, nF, fd.fx, fd.fl, g.cell, g.sfx,
+                       g.sfl);
+    return hipGetLastError();
+}
 
 hipError_t launch_near64(const PairJob* jobs, int njobs, double alpha, double beta, bool grad, hipStream_t s)
 {
-    const dim3 block(kNearI);
+    const dim3 block(kNearBlock);
     const bool gen = !is_p6(alpha, beta);
     return for_each_batch(jobs, njobs, [&](const PairBatch& jb, dim3 grid) {
         if (grad) {
