@@ -29,6 +29,7 @@ namespace tp {
 
 constexpr int kCgBlock = 256;
 constexpr int kMaxW = 128;           // workgroups per column group
+static_assert(kMaxW <= kMaxBarrierW, "one barrier flag per workgroup");
 constexpr int kMaxGroups = 8;
 
 struct CgArgs {
@@ -185,7 +186,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs A)
         }
         block_sums2<KG>(loc, dum, sh_wave, sh_sum);
         if (threadIdx.x < 2 * KG) redbuf()[w * 2 * KG + threadIdx.x] = sh_sum[threadIdx.x];
-        if (!group_barrier(gbar, w, A.W, A.flags)) return;
+        if (!group_barrier(gbar, w, A.W, A.flags, (unsigned)bcount + 1u)) return;
         group_sum(redbuf());
         ++bcount;
         bool all = true;
@@ -222,7 +223,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs A)
         }
         block_sums2<KG>(ga, de, sh_wave, sh_sum);
         if (threadIdx.x < 2 * KG) redbuf()[w * 2 * KG + threadIdx.x] = sh_sum[threadIdx.x];
-        if (!group_barrier(gbar, w, A.W, A.flags)) return;
+        if (!group_barrier(gbar, w, A.W, A.flags, (unsigned)bcount + 1u)) return;
         group_sum(redbuf());
         ++bcount;
 #pragma unroll
@@ -282,7 +283,7 @@ __global__ __launch_bounds__(kCgBlock) void k_cg(CgArgs A)
             }
             block_sums2<KG>(ga, de, sh_wave, sh_sum);
             if (threadIdx.x < 2 * KG) redbuf()[w * 2 * KG + threadIdx.x] = sh_sum[threadIdx.x];
-            if (!group_barrier(gbar, w, A.W, A.flags)) return;
+            if (!group_barrier(gbar, w, A.W, A.flags, (unsigned)bcount + 1u)) return;
             group_sum(redbuf());
             ++bcount;
             bool conv = true;

@@ -341,9 +341,9 @@ int near_block_faces();           // faces S per near-field workgroup (n_itiles 
 
 constexpr unsigned long long kSpinLimit = 1ull << 22;
 constexpr int kLine = 32;            // unsigned words per 128-byte line
-// barrier words of one group: 8 level-1 counters, 1 level-2 counter, 1 generation,
-// each on its own line
-constexpr int kBarWordsPerGroup = 10 * kLine;
+// barrier words of one group: one flag line per workgroup, at most kMaxBarrierW workgroups
+constexpr int kMaxBarrierW = 256;
+constexpr int kBarWordsPerGroup = kMaxBarrierW * kLine;
 
 #if defined(__HIPCC__)
 // Sum of a double over the 64 lanes of a wave in a fixed order, returned uniformly:
@@ -372,61 +372,51 @@ __device__ __forceinline__ double wave_sum(double v)
     return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
-// Two-level barrier among the W workgroups of a group: workgroup w first arrives at
-// counter (w % 8); the last of that set arrives at the group counter; the last of those
-// advances the generation word that everybody waits on.
-__device__ __forceinline__ bool group_barrier(unsigned* gbar, int w, int W, int* flags)
+// Barrier among the W workgroups of a group, the target-th of the launch (1, 2, ...): every
+// workgroup raises its own flag word (one 128-byte line each, zeroed before the launch) to
+// target, then all its threads poll the W flags (a few each) until all have reached it.
+// No atomic read-modify-write is involved, so arrivals do not serialise on a counter.
+// The workgroup barrier alone does not wait for global stores (it only orders them for
+// waves of the same CU), and a release by thread 0 waits for its own wave's stores only:
+// so every wave first waits until its own stores have been acknowledged by L2
+// (s_waitcnt vmcnt(0), immediate 0x0F70: expcnt and lgkmcnt at their maxima); thread 0's
+// agent-scope release store of the flag (L2 write-back first) then covers the stores of the
+// whole workgroup, and its acquire fence after the wait makes the other workgroups' stores
+// visible to the whole workgroup (the caches it invalidates are shared by the workgroup's
+// waves).  Spins are bounded: a wait that exceeds kSpinLimit, or sees the abort flag, sets
+// the abort flag and returns false in every workgroup.
+__device__ __forceinline__ bool group_barrier(unsigned* gbar, int w, int W, int* flags, unsigned target)
 {
-    // The workgroup barrier alone does not wait for global stores (it only orders them for
-    // waves of the same CU), and a release by thread 0 waits for its own wave's stores only.
-    // So every wave first waits until its own stores have been acknowledged by L2
-    // (s_waitcnt vmcnt(0), immediate 0x0F70: expcnt and lgkmcnt at their maxima); thread 0's
-    // agent-scope release (L2 write-back) then covers the stores of the whole workgroup,
-    // and its acquire fence after the wait makes the other workgroups' stores visible to the
-    // whole workgroup (the caches it invalidates are shared by the workgroup's waves).
     __shared__ int ok_sh;
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
     if (threadIdx.x == 0) {
-        int ok = 1;
-        unsigned* gen = gbar + 9 * kLine;
-        unsigned* top = gbar + 8 * kLine;
-        const int sub = w & 7;
-        const int nsub = (W + 7 - sub) / 8;           // members of this level-1 set
-        const int ntop = W < 8 ? W : 8;                 // non-empty level-1 sets
-        const unsigned g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        unsigned* c1 = gbar + sub * kLine;
-        const unsigned a1 = __hip_atomic_fetch_add(c1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        bool last = false;
-        if ((int)a1 + 1 == nsub) {
-            __hip_atomic_store(c1, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            const unsigned a2 = __hip_atomic_fetch_add(top, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-            if ((int)a2 + 1 == ntop) {
-                __hip_atomic_store(top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_store(gen, g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-                last = true;
+        __hip_atomic_store(gbar + (size_t)w * kLine, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        ok_sh = 1;
+    }
+    __syncthreads();
+    bool bad = false;
+    for (int q = threadIdx.x; q < W && !bad; q += blockDim.x) {
+        unsigned long long spins = 0;
+        while (__hip_atomic_load(gbar + (size_t)q * kLine, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            ++spins;
+            if (spins > kSpinLimit ||
+                ((spins & 255ull) == 0ull &&
+                 __hip_atomic_load(&flags[kFlagCgAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                bad = true;
+                break;
             }
         }
-        if (!last) {
-            unsigned long long spins = 0;
-            while (__hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                __builtin_amdgcn_s_sleep(1);
-                ++spins;
-                if (spins > kSpinLimit) {
-                    ok = 0;
-                    break;
-                }
-                if ((spins & 255ull) == 0ull &&
-                    __hip_atomic_load(&flags[kFlagCgAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ok = 0;
-                    break;
-                }
-            }
-            if (!ok) __hip_atomic_store(&flags[kFlagCgAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+    }
+    if (bad) {
+        __hip_atomic_store(&flags[kFlagCgAbort], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok_sh = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        if (__hip_atomic_load(&flags[kFlagCgAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-        ok_sh = ok;
+        if (__hip_atomic_load(&flags[kFlagCgAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok_sh = 0;
     }
     __syncthreads();
     return ok_sh != 0;

@@ -39,6 +39,7 @@ namespace tp {
 constexpr int kBS = 128;            // vertices per block = threads per solver workgroup
 constexpr int kMaxNbn = 32;         // neighbouring blocks of a block (itself included)
 constexpr int kMaxNbPcg = 256;      // blocks (one co-resident workgroup per block)
+static_assert(kMaxNbPcg <= kMaxBarrierW, "one barrier flag per block");
 
 // ---------------------------------------------------------------- per-geometry setup
 
@@ -377,7 +378,7 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
     auto pub = [&]() { return nbar & 1; };
     auto got = [&]() { return (nbar - 1) & 1; };
     auto sync = [&]() -> bool {
-        const bool ok = group_barrier(A.bar, B, nb, A.flags);
+        const bool ok = group_barrier(A.bar, B, nb, A.flags, (unsigned)nbar + 1u);
         ++nbar;
         return ok;
     };
