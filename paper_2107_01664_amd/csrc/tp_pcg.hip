@@ -36,7 +36,8 @@
 
 namespace tp {
 
-constexpr int kBS = 128;            // vertices per block = threads per solver workgroup
+constexpr int kBS = 128;            // vertices per block = row-owning threads of a solver workgroup
+constexpr int kThreads = 2 * kBS;   // threads per solver workgroup: row owners + helpers
 constexpr int kMaxNbn = 32;         // neighbouring blocks of a block (itself included)
 constexpr int kMaxNbPcg = 256;      // blocks (one co-resident workgroup per block)
 static_assert(kMaxNbPcg <= kMaxBarrierW, "one barrier flag per block");
@@ -58,7 +59,8 @@ __global__ void k_perm_ell_vals(int64_t n, int w, const int32_t* __restrict__ pe
 
 // Dense inverse of each diagonal block (Gauss-Jordan in LDS; the block is symmetric
 // positive definite, or made so by the rank-one term, so no pivoting is needed).
-__global__ __launch_bounds__(256) void k_block_inverse(int64_t n, int w, const int32_t* __restrict__ pcol,
+constexpr int kInvThreads = 256;
+__global__ __launch_bounds__(kInvThreads) void k_block_inverse(int64_t n, int w, const int32_t* __restrict__ pcol,
                                                        const double* __restrict__ pval,
                                                        const int32_t* __restrict__ bstart,
                                                        const int32_t* __restrict__ whole,
@@ -68,9 +70,9 @@ __global__ __launch_bounds__(256) void k_block_inverse(int64_t n, int w, const i
     __shared__ double fcol[kBS];
     const int B = blockIdx.x;
     const int32_t s0 = bstart[B], cnt = bstart[B + 1] - s0;
-    for (int t = threadIdx.x; t < kBS * kBS; t += blockDim.x) A[t] = 0.0;
+    for (int t = threadIdx.x; t < kBS * kBS; t += kInvThreads) A[t] = 0.0;
     __syncthreads();
-    for (int t = threadIdx.x; t < kBS; t += blockDim.x) {
+    for (int t = threadIdx.x; t < kBS; t += kInvThreads) {
         if (t < cnt) {
             const int64_t i = s0 + t;
             for (int e = 0; e < w; ++e) {
@@ -92,31 +94,32 @@ __global__ __launch_bounds__(256) void k_block_inverse(int64_t n, int w, const i
         }
         __syncthreads();
         const double add = dsum / cnt;
-        for (int t = threadIdx.x; t < cnt * cnt; t += blockDim.x) A[(t / cnt) * kBS + (t % cnt)] += add;
+        for (int t = threadIdx.x; t < cnt * cnt; t += kInvThreads) A[(t / cnt) * kBS + (t % cnt)] += add;
         __syncthreads();
     }
     for (int k = 0; k < kBS; ++k) {
         const double p = 1.0 / A[k * kBS + k];
         __syncthreads();
-        for (int j = threadIdx.x; j < kBS; j += blockDim.x) {
-            fcol[j] = A[j * kBS + k];           // column k before the update
-        }
+        if (threadIdx.x < kBS) fcol[threadIdx.x] = A[threadIdx.x * kBS + k];   // column k before the update
         __syncthreads();
-        for (int j = threadIdx.x; j < kBS; j += blockDim.x)
-            A[k * kBS + j] = (j == k ? 1.0 : A[k * kBS + j]) * p;
+        if (threadIdx.x < kBS) A[k * kBS + threadIdx.x] = (threadIdx.x == k ? 1.0 : A[k * kBS + threadIdx.x]) * p;
         __syncthreads();
-        for (int t = threadIdx.x; t < kBS * kBS; t += blockDim.x) {
-            const int i = t / kBS, j = t - i * kBS;
+        // each thread updates kBS * kBS / kInvThreads entries of one column, all loads issued
+        // together
+        const int j = threadIdx.x & (kBS - 1);
+        const double akj = A[k * kBS + j];
+#pragma unroll 16
+        for (int i = threadIdx.x / kBS; i < kBS; i += kInvThreads / kBS) {
             if (i != k) {
                 const double base = (j == k) ? 0.0 : A[i * kBS + j];
-                A[i * kBS + j] = base - fcol[i] * A[k * kBS + j];
+                A[i * kBS + j] = base - fcol[i] * akj;
             }
         }
         __syncthreads();
     }
     // symmetrize (the elimination leaves rounding-level asymmetry) and round to FP32
     float* dst = Binv + (int64_t)B * kBS * kBS;
-    for (int t = threadIdx.x; t < kBS * kBS; t += blockDim.x) {
+    for (int t = threadIdx.x; t < kBS * kBS; t += kInvThreads) {
         const int i = t / kBS, j = t - i * kBS;
         dst[t] = (float)(0.5 * (A[i * kBS + j] + A[j * kBS + i]));
     }
@@ -150,58 +153,134 @@ __global__ __launch_bounds__(64) void k_coarse_rows(int64_t n, int w, int nb, co
     for (int t = threadIdx.x; t < nb; t += blockDim.x) C0[(int64_t)B * nb + t] = acc[t];
 }
 
-// Inverse of the nb x nb coarse matrix after adding the per-component rank-one terms, by
-// Gauss-Jordan elimination in one workgroup: in LDS when the matrix fits (nb <= kCoarseLdsMax),
-// else in global memory.  The rank-one scale of a component of several blocks is the mean
-// diagonal of the coarse matrix over such blocks; a component of one block has a zero
-// coarse entry (C is singular on its constants), so it gets the block's own diagonal sum of
-// C instead (any positive scale gives the same action on mean-zero vectors; this one keeps
-// rounding errors of the block sums from being amplified).
+// Inverse of the nb x nb coarse matrix after adding the per-component rank-one terms.  The
+// rank-one scale of a component of several blocks is the mean diagonal of the coarse matrix
+// over such blocks; a component of one block has a zero coarse entry (C is singular on its
+// constants), so it gets the block's own diagonal sum of C instead (any positive scale gives
+// the same action on mean-zero vectors; this one keeps rounding errors of the block sums from
+// being amplified).  The matrix is symmetric positive definite, so no pivoting is needed.
 constexpr int kCoarseThreads = 1024;
-constexpr int kCoarseLdsMax = 140;          // 140 x 140 doubles = 153 KB of LDS
+constexpr int kCoarseSweepMax = 200;   // packed upper triangle: 200 x 201 / 2 doubles = 157 KB of LDS
 
-template <bool LDS>
+__device__ __forceinline__ double coarse_entry(const double* __restrict__ G, int nb, int i, int j,
+                                               const int32_t* __restrict__ bcomp,
+                                               const int32_t* __restrict__ ncomp_blocks,
+                                               const double* __restrict__ bdiag, double dmean)
+{
+    // the block sums of the two triangles may differ in the last bit: their mean is used
+    double v = 0.5 * (G[(int64_t)i * nb + j] + G[(int64_t)j * nb + i]);
+    if (bcomp[i] == bcomp[j]) {
+        const int nc = ncomp_blocks[bcomp[i]];
+        v += nc > 1 ? dmean / nc : bdiag[i];
+    }
+    return v;
+}
+
+__device__ double coarse_dmean(const double* __restrict__ G, int nb, const int32_t* __restrict__ bcomp,
+                               const int32_t* __restrict__ ncomp_blocks)
+{
+    double s = 0.0;
+    int cnt = 0;
+    for (int i = 0; i < nb; ++i)
+        if (ncomp_blocks[bcomp[i]] > 1) {
+            s += G[(int64_t)i * nb + i];
+            ++cnt;
+        }
+    return cnt > 0 ? s / cnt : 0.0;
+}
+
+// nb <= kCoarseSweepMax: symmetric sweeps in LDS on the packed upper triangle (row i holds
+// columns i .. nb-1).  Sweeping pivot k with d = a_kk maps a_ij -> a_ij - a_ik a_kj / d
+// (i, j != k), a_ik -> a_ik / d, a_kk -> -1 / d; after all pivots the matrix is -A^{-1}.
+// Rows are spread over the waves, columns over the lanes.
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_sweep(int nb, const int32_t* __restrict__ bcomp,
+                                                                 const int32_t* __restrict__ ncomp_blocks,
+                                                                 const double* __restrict__ bdiag,
+                                                                 double* __restrict__ G)
+{
+    extern __shared__ __align__(16) double A[];
+    __shared__ double fcol[kMaxNbPcg];
+    __shared__ double dmean_sh;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    constexpr int kWaves = kCoarseThreads / 64;
+    auto off = [&](int i) { return i * nb - (i * (i - 1)) / 2; };
+    if (threadIdx.x == 0) dmean_sh = coarse_dmean(G, nb, bcomp, ncomp_blocks);
+    __syncthreads();
+    const double dmean = dmean_sh;
+    for (int i = wave; i < nb; i += kWaves)
+        for (int j = i + lane; j < nb; j += 64) A[off(i) + j - i] = coarse_entry(G, nb, i, j, bcomp, ncomp_blocks, bdiag, dmean);
+    __syncthreads();
+    for (int k = 0; k < nb; ++k) {
+        const double d = A[off(k)];
+        if ((int)threadIdx.x < nb) {
+            const int i = threadIdx.x;
+            fcol[i] = i <= k ? A[off(i) + k - i] : A[off(k) + i - k];
+        }
+        __syncthreads();
+        const double invd = 1.0 / d;
+        for (int i = wave; i < nb; i += kWaves) {
+            const double fi = fcol[i];
+            for (int j = i + lane; j < nb; j += 64) {
+                const int idx = off(i) + j - i;
+                double v;
+                if (i == k && j == k) v = -invd;
+                else if (i == k) v = fcol[j] * invd;
+                else if (j == k) v = fi * invd;
+                else v = A[idx] - fi * fcol[j] * invd;
+                A[idx] = v;
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = wave; i < nb; i += kWaves)
+        for (int j = i + lane; j < nb; j += 64) {
+            const double v = -A[off(i) + j - i];
+            G[(int64_t)i * nb + j] = v;
+            G[(int64_t)j * nb + i] = v;
+        }
+}
+
+// nb > kCoarseSweepMax: Gauss-Jordan elimination on the full matrix in global memory.
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(int nb, const int32_t* __restrict__ bcomp,
                                                                    const int32_t* __restrict__ ncomp_blocks,
                                                                    const double* __restrict__ bdiag,
                                                                    double* __restrict__ G)
 {
-    extern __shared__ __align__(16) double Ash[];
     __shared__ double fcol[kMaxNbPcg];
-    __shared__ double dmean;
-    double* A = LDS ? Ash : G;
+    __shared__ double dmean_sh;
     const int nn = nb * nb;
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        int cnt = 0;
-        for (int i = 0; i < nb; ++i)
-            if (ncomp_blocks[bcomp[i]] > 1) {
-                s += G[(int64_t)i * nb + i];
-                ++cnt;
-            }
-        dmean = cnt > 0 ? s / cnt : 0.0;
-    }
+    if (threadIdx.x == 0) dmean_sh = coarse_dmean(G, nb, bcomp, ncomp_blocks);
     __syncthreads();
-    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
-        const int i = t / nb, j = t - i * nb;
-        double v = G[t];
-        if (bcomp[i] == bcomp[j]) {
-            const int nc = ncomp_blocks[bcomp[i]];
-            v += nc > 1 ? dmean / nc : bdiag[i];
+    const double dmean = dmean_sh;
+    // symmetrised entries with the rank-one terms: the upper triangle first (each pair read
+    // and written by one thread), then the diagonal and the mirrored lower triangle
+    double* A = G;
+    {
+        for (int t = threadIdx.x; t < nn; t += kCoarseThreads) {
+            const int i = t / nb, j = t - i * nb;
+            if (i < j) A[t] = coarse_entry(G, nb, i, j, bcomp, ncomp_blocks, bdiag, dmean);
         }
-        A[t] = v;
+        __threadfence_block();
+        __syncthreads();
+        for (int t = threadIdx.x; t < nn; t += kCoarseThreads) {
+            const int i = t / nb, j = t - i * nb;
+            if (i == j) A[t] += ncomp_blocks[bcomp[i]] > 1 ? dmean / ncomp_blocks[bcomp[i]] : bdiag[i];
+            else if (i > j) A[t] = A[(int64_t)j * nb + i];
+        }
+        __threadfence_block();
+        __syncthreads();
     }
-    __syncthreads();
     for (int k = 0; k < nb; ++k) {
         const double p = 1.0 / A[(int64_t)k * nb + k];
         __syncthreads();
-        for (int j = threadIdx.x; j < nb; j += blockDim.x) fcol[j] = A[(int64_t)j * nb + k];
+        for (int j = threadIdx.x; j < nb; j += kCoarseThreads) fcol[j] = A[(int64_t)j * nb + k];
         __syncthreads();
-        for (int j = threadIdx.x; j < nb; j += blockDim.x)
+        for (int j = threadIdx.x; j < nb; j += kCoarseThreads)
             A[(int64_t)k * nb + j] = (j == k ? 1.0 : A[(int64_t)k * nb + j]) * p;
         __threadfence_block();
         __syncthreads();
-        for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+#pragma unroll 8
+        for (int t = threadIdx.x; t < nn; t += kCoarseThreads) {
             const int i = t / nb, j = t - i * nb;
             if (i != k) {
                 const double base = (j == k) ? 0.0 : A[t];
@@ -211,8 +290,6 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(int nb, const
         __threadfence_block();
         __syncthreads();
     }
-    if (LDS)
-        for (int t = threadIdx.x; t < nn; t += blockDim.x) G[t] = A[t];
 }
 
 // forward: dst[i][c] = src[perm[i]][c0 + c] (dst in block order, row stride k);
@@ -266,9 +343,9 @@ struct PcgShared {
     double r[kBS * KG];
     double rho[kMaxNbPcg * KG];
     double c[kMaxNbn * KG];
-    double wave[2 * 3 * KG];
+    double wave[(kThreads / 64) * 3 * KG];
     double sums[3 * KG];
-    double part[kBS];
+    double part[kThreads];
     int32_t nbl[kMaxNbn];
 };
 
@@ -306,8 +383,8 @@ __device__ __forceinline__ double dot_fixed(const double* __restrict__ a, const 
     return (a0 + a1) + (a2 + a3);
 }
 
-// Fixed-order workgroup reduction of M values per thread (kBS = 128 threads, two waves):
-// butterfly within each wave, then wave 0 + wave 1.  Result in out[0 .. M).
+// Fixed-order workgroup reduction of M values per thread (kThreads threads): butterfly
+// within each wave, then the waves added in order.  Result in out[0 .. M).
 template <int M>
 __device__ __forceinline__ void wg_reduce(const double (&v)[M], double* wave_sh, double* out)
 {
@@ -318,7 +395,12 @@ __device__ __forceinline__ void wg_reduce(const double (&v)[M], double* wave_sh,
         if (lane == 0) wave_sh[wave * M + q] = s;
     }
     __syncthreads();
-    if ((int)threadIdx.x < M) out[threadIdx.x] = wave_sh[threadIdx.x] + wave_sh[M + threadIdx.x];
+    if ((int)threadIdx.x < M) {
+        double a = wave_sh[threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < kThreads / 64; ++w) a += wave_sh[w * M + threadIdx.x];
+        out[threadIdx.x] = a;
+    }
     __syncthreads();
 }
 
@@ -326,7 +408,7 @@ __device__ __forceinline__ void wg_reduce(const double (&v)[M], double* wave_sh,
 // [tab[m].block0, tab[m + 1].block0) and synchronises only among them (its own barrier
 // words), so its iterates are those of a launch of its own.
 template <int KG>
-__global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, int ntab)
+__global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ tab, int ntab)
 {
     extern __shared__ __align__(16) char smem_raw[];
     PcgShared<KG>& S = *reinterpret_cast<PcgShared<KG>*>(smem_raw);
@@ -338,6 +420,8 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
     const int nb = A.nb, k = A.k;
     const int64_t n = A.n;
     const int32_t s0 = A.bstart[B], cnt = A.bstart[B + 1] - s0;
+    // threads t < kBS own row s0 + t of the block (when t < cnt); threads kBS .. kThreads
+    // help with the block product, the coarse values and the cross-block sums
     const int t = threadIdx.x;
     const bool act = t < cnt;
     const int64_t i = s0 + t;
@@ -345,15 +429,15 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
     {
         const float4* src = reinterpret_cast<const float4*>(A.Binv + (int64_t)B * kBS * kBS);
         float4* dst = reinterpret_cast<float4*>(S.Binv);
-        for (int q = t; q < kBS * kBS / 4; q += kBS) dst[q] = src[q];
+        for (int q = t; q < kBS * kBS / 4; q += kThreads) dst[q] = src[q];
     }
     const int nbo = A.badj_off[B], nbn = A.badj_off[B + 1] - nbo;
-    for (int q = t; q < nbn; q += kBS) S.nbl[q] = A.badj[nbo + q];
+    for (int q = t; q < nbn; q += kThreads) S.nbl[q] = A.badj[nbo + q];
     __syncthreads();
     // rows of C0inv for the neighbouring blocks stay in LDS when they fit
     const bool crow_lds = (int64_t)nbn * nb <= kCrowMax;
     if (crow_lds)
-        for (int q = t; q < nbn * nb; q += kBS) S.crow[q] = A.C0inv[(int64_t)S.nbl[q / nb] * nb + (q % nb)];
+        for (int q = t; q < nbn * nb; q += kThreads) S.crow[q] = A.C0inv[(int64_t)S.nbl[q / nb] * nb + (q % nb)];
     __syncthreads();
     int own_slot = 0;
     for (int q = 0; q < nbn; ++q)
@@ -369,6 +453,19 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
         cj[e] = in ? A.pcol[(int64_t)e * n + i] : 0;
         cv[e] = in ? A.pval[(int64_t)e * n + i] : 0.0;
         cs[e] = in ? A.pslot[(int64_t)e * n + i] : 0;
+    }
+    // coarse part of a row of C M^{-1}: the row's entries added per neighbouring block (the
+    // first entry of each block carries the block's weight, the others weight 0)
+    double cw[kCache];
+#pragma unroll
+    for (int e = 0; e < kCache; ++e) {
+        bool first = true;
+#pragma unroll
+        for (int f = 0; f < e; ++f) first = first && (cs[f] != cs[e] || f >= A.ell_w);
+        double w = 0.0;
+#pragma unroll
+        for (int f = e; f < kCache; ++f) w += (cs[f] == cs[e] && f < A.ell_w) ? cv[f] : 0.0;
+        cw[e] = (first && e < A.ell_w) ? w : 0.0;
     }
 
     // Exchange buffers come in two copies: data published before the b-th barrier goes to
@@ -392,7 +489,7 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
     auto grid_sum = [&](auto mtag, int c) {
         constexpr int M = decltype(mtag)::value;
         const double* red = redb(c);
-        constexpr int P = kBS / M;
+        constexpr int P = kThreads / M;
         const int chunk = (nb + P - 1) / P;
         const int q = t / P, part = t - q * P;
         if (q < M) {
@@ -418,28 +515,42 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
     // neighbouring blocks).
     auto round = [&](const double (&y)[KG]) -> bool {
         const int cp = pub();
+        if (t < kBS) {
 #pragma unroll
-        for (int c = 0; c < KG; ++c) S.r[t * KG + c] = (act && c < k) ? y[c] : 0.0;
+            for (int c = 0; c < KG; ++c) S.r[t * KG + c] = (act && c < k) ? y[c] : 0.0;
+        }
         __syncthreads();
         double v[KG];
 #pragma unroll
         for (int c = 0; c < KG; ++c) v[c] = 0.0;
         // padding rows of the block hold y = 0 and an identity block in C_BB^{-1}, so the
-        // product runs over all kBS rows with a fixed trip count
-        // chunks of CH rows: all LDS loads of a chunk are issued before its FMAs
+        // product runs over all kBS rows with a fixed trip count.  Row tt's sum is split in
+        // two halves of j (owner: j < kBS / 2, helper tt + kBS: the rest), added in that
+        // order; chunks of CH rows: all LDS loads of a chunk are issued before its FMAs.
+        const int tt = t & (kBS - 1), jbeg = (t / kBS) * (kBS / 2);
         constexpr int CH = KG <= 3 ? 8 : (KG <= 6 ? 4 : 2);
 #pragma unroll 1
-        for (int j0 = 0; j0 < kBS; j0 += CH) {
+        for (int j0 = jbeg; j0 < jbeg + kBS / 2; j0 += CH) {
             float bj[CH];
             double yj[CH * KG];
 #pragma unroll
-            for (int q = 0; q < CH; ++q) bj[q] = S.Binv[(j0 + q) * kBS + t];
+            for (int q = 0; q < CH; ++q) bj[q] = S.Binv[(j0 + q) * kBS + tt];
 #pragma unroll
             for (int q = 0; q < CH * KG; ++q) yj[q] = S.r[j0 * KG + q];
 #pragma unroll
             for (int q = 0; q < CH; ++q)
 #pragma unroll
                 for (int c = 0; c < KG; ++c) v[c] += (double)bj[q] * yj[q * KG + c];
+        }
+        // the helpers' halves go through S.rho, which is free until the block sums arrive
+        if (t >= kBS) {
+#pragma unroll
+            for (int c = 0; c < KG; ++c) S.rho[tt * KG + c] = v[c];
+        }
+        __syncthreads();
+        if (t < kBS) {
+#pragma unroll
+            for (int c = 0; c < KG; ++c) v[c] += S.rho[t * KG + c];
         }
         double tmp[KG];
 #pragma unroll
@@ -454,24 +565,24 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
         const double* Vb = vbuf(cp);
         const double* rho = rhob(cp);
         // block sums of every block: four loads in flight per thread
-        for (int q0 = t; q0 < nb * KG; q0 += 4 * kBS) {
+        for (int q0 = t; q0 < nb * KG; q0 += 4 * kThreads) {
             double vv[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int qq = q0 + u * kBS, bb = qq / KG, c = qq - bb * KG;
+                const int qq = q0 + u * kThreads, bb = qq / KG, c = qq - bb * KG;
                 vv[u] = (qq < nb * KG && c < k) ? rho[(int64_t)bb * k + c] : 0.0;
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (q0 + u * kBS < nb * KG) S.rho[q0 + u * kBS] = vv[u];
+                if (q0 + u * kThreads < nb * KG) S.rho[q0 + u * kThreads] = vv[u];
         }
         __syncthreads();
         // coarse values c(sl) = sum_bb C0inv[nbl[sl]][bb] rho[bb] for the nbn x KG jobs: each
         // job's dot product is cut into P parts of consecutive blocks (one per thread)
         const int jobs = nbn * KG;
-        for (int j0 = 0; j0 < jobs; j0 += kBS) {
-            const int nj = min(kBS, jobs - j0);
-            const int P = max(1, kBS / nj);
+        for (int j0 = 0; j0 < jobs; j0 += kThreads) {
+            const int nj = min(kThreads, jobs - j0);
+            const int P = max(1, kThreads / nj);
             const int chunk = (nb + P - 1) / P;
             const int jl = t / P, part = t - jl * P;
             if (jl < nj) {
@@ -497,9 +608,15 @@ __global__ __launch_bounds__(kBS) void k_pcg(const PcgArgs* __restrict__ tab, in
                     const double* vj = Vb + (int64_t)cj[e] * k;
 #pragma unroll
                     for (int c = 0; c < KG; ++c)
-                        if (c < k) acc[c] += cv[e] * (vj[c] + S.c[cs[e] * KG + c]);
+                        if (c < k) acc[c] += cv[e] * vj[c];
                 }
             }
+#pragma unroll
+            for (int e = 0; e < kCache; ++e)
+                if (cw[e] != 0.0) {
+#pragma unroll
+                    for (int c = 0; c < KG; ++c) acc[c] += cw[e] * S.c[cs[e] * KG + c];
+                }
             for (int e = kCache; e < A.ell_w; ++e) {
                 const int32_t j = A.pcol[(int64_t)e * n + i];
                 const double a = A.pval[(int64_t)e * n + i];
@@ -698,15 +815,15 @@ hipError_t launch_pcg_setup(const PcgSetup& ps, const int32_t* lap_off, const do
     hipLaunchKernelGGL(k_coarse_rows, dim3(ps.nb), dim3(64), sizeof(double) * ps.nb, s, ps.n, ps.ell_w,
                        ps.nb, ps.pcol, ps.pval, ps.bstart, ps.blk, ps.C0inv, bdiag);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ps.nb <= kCoarseLdsMax) {
-        const size_t sm = sizeof(double) * (size_t)ps.nb * ps.nb;
-        e = hipFuncSetAttribute((const void*)k_coarse_inverse<true>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(double) * kCoarseLdsMax * kCoarseLdsMax));
+    if (ps.nb <= kCoarseSweepMax) {
+        const size_t sm = sizeof(double) * (size_t)ps.nb * (ps.nb + 1) / 2;
+        e = hipFuncSetAttribute((const void*)k_coarse_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(sizeof(double) * kCoarseSweepMax * (kCoarseSweepMax + 1) / 2));
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_coarse_inverse<true>, dim3(1), dim3(kCoarseThreads), sm, s, ps.nb, ps.bcomp,
+        hipLaunchKernelGGL(k_coarse_sweep, dim3(1), dim3(kCoarseThreads), sm, s, ps.nb, ps.bcomp,
                            ps.ncomp_blocks, bdiag, ps.C0inv);
     } else {
-        hipLaunchKernelGGL(k_coarse_inverse<false>, dim3(1), dim3(kCoarseThreads), 0, s, ps.nb, ps.bcomp,
+        hipLaunchKernelGGL(k_coarse_inverse, dim3(1), dim3(kCoarseThreads), 0, s, ps.nb, ps.bcomp,
                            ps.ncomp_blocks, bdiag, ps.C0inv);
     }
     return hipGetLastError();
@@ -755,7 +872,7 @@ hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, v
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kBS, smem);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, smem);
     if (e != hipSuccess) return e;
     const int64_t cap = (int64_t)per_cu * device_info().num_cu;
     PcgArgs* H = static_cast<PcgArgs*>(tab_host);
@@ -795,7 +912,7 @@ hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, v
         int blocks = 0;
         for (int m = g.first; m < g.second; ++m) blocks += H[m].nb;
         void* params[] = {(void*)&t, (void*)&nt};
-        e = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kBS), params, smem, s);
+        e = hipLaunchCooperativeKernel(fn, dim3(blocks), dim3(kThreads), params, smem, s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
