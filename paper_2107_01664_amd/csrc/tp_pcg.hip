@@ -564,6 +564,17 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         if (!sync()) return false;
         const double* Vb = vbuf(cp);
         const double* rho = rhob(cp);
+        // with few columns, the neighbours' block solves are loaded now, so that their
+        // latency overlaps the block sums' load and the coarse values
+        constexpr bool kEarly = KG <= 4;
+        double vnb[kEarly ? kCache : 1][KG];
+        if (kEarly && act) {
+#pragma unroll
+            for (int e = 0; e < (kEarly ? kCache : 1); ++e)
+#pragma unroll
+                for (int c = 0; c < KG; ++c)
+                    vnb[e][c] = (e < A.ell_w && c < k) ? Vb[(int64_t)cj[e] * k + c] : 0.0;
+        }
         // block sums of every block: four loads in flight per thread
         for (int q0 = t; q0 < nb * KG; q0 += 4 * kThreads) {
             double vv[4];
@@ -602,13 +613,20 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
             acc[c] = 0.0;
         }
         if (act) {
+            if (kEarly) {
 #pragma unroll
-            for (int e = 0; e < kCache; ++e) {
-                if (e < A.ell_w) {
-                    const double* vj = Vb + (int64_t)cj[e] * k;
+                for (int e = 0; e < (kEarly ? kCache : 1); ++e)
 #pragma unroll
-                    for (int c = 0; c < KG; ++c)
-                        if (c < k) acc[c] += cv[e] * vj[c];
+                    for (int c = 0; c < KG; ++c) acc[c] += cv[e] * vnb[e][c];
+            } else {
+#pragma unroll
+                for (int e = 0; e < kCache; ++e) {
+                    if (e < A.ell_w) {
+                        const double* vj = Vb + (int64_t)cj[e] * k;
+#pragma unroll
+                        for (int c = 0; c < KG; ++c)
+                            if (c < k) acc[c] += cv[e] * vj[c];
+                    }
                 }
             }
 #pragma unroll
