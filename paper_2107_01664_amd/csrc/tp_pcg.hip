@@ -345,6 +345,8 @@ struct PcgShared {
     double c[kMaxNbn * KG];
     double wave[(kThreads / 64) * 3 * KG];
     double sums[3 * KG];
+    double coef[2 * KG];            // alpha, beta of every column
+    int live[KG];                   // column not yet converged
     double part[kThreads];
     int32_t nbl[kMaxNbn];
 };
@@ -564,13 +566,12 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         if (!sync()) return false;
         const double* Vb = vbuf(cp);
         const double* rho = rhob(cp);
-        // with few columns, the neighbours' block solves are loaded now, so that their
-        // latency overlaps the block sums' load and the coarse values
-        constexpr bool kEarly = KG <= 4;
-        double vnb[kEarly ? kCache : 1][KG];
-        if (kEarly && act) {
+        // the neighbours' block solves are loaded now, so that their latency overlaps the
+        // block sums' load and the coarse values
+        double vnb[kCache][KG];
+        if (act) {
 #pragma unroll
-            for (int e = 0; e < (kEarly ? kCache : 1); ++e)
+            for (int e = 0; e < kCache; ++e)
 #pragma unroll
                 for (int c = 0; c < KG; ++c)
                     vnb[e][c] = (e < A.ell_w && c < k) ? Vb[(int64_t)cj[e] * k + c] : 0.0;
@@ -613,22 +614,10 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
             acc[c] = 0.0;
         }
         if (act) {
-            if (kEarly) {
 #pragma unroll
-                for (int e = 0; e < (kEarly ? kCache : 1); ++e)
+            for (int e = 0; e < kCache; ++e)
 #pragma unroll
-                    for (int c = 0; c < KG; ++c) acc[c] += cv[e] * vnb[e][c];
-            } else {
-#pragma unroll
-                for (int e = 0; e < kCache; ++e) {
-                    if (e < A.ell_w) {
-                        const double* vj = Vb + (int64_t)cj[e] * k;
-#pragma unroll
-                        for (int c = 0; c < KG; ++c)
-                            if (c < k) acc[c] += cv[e] * vj[c];
-                    }
-                }
-            }
+                for (int c = 0; c < KG; ++c) acc[c] += cv[e] * vnb[e][c];
 #pragma unroll
             for (int e = 0; e < kCache; ++e)
                 if (cw[e] != 0.0) {
@@ -710,20 +699,16 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         return true;
     };
 
+    // Thread c < KG keeps the scalars of column c (|b|^2, last |r|^2, gamma, alpha, state,
+    // iterations) and forms its alpha and beta; the others read them from LDS.
     const double rtol2 = A.rtol * A.rtol;
-    double bb[KG], rr[KG], gam[KG], alpha[KG];
-    bool done[KG];
-    int its[KG];
+    double my_bb = 0.0, my_rr = 0.0, my_gam = 0.0, my_alpha = 0.0;
+    bool my_done = false;
+    int my_its = 0;
 #pragma unroll
     for (int c = 0; c < KG; ++c) {
         r[c] = (act && c < k) ? A.b[i * k + c] : 0.0;
         x[c] = 0.0;
-        its[c] = 0;
-        bb[c] = 0.0;
-        rr[c] = 0.0;
-        gam[c] = 0.0;
-        alpha[c] = 0.0;
-        done[c] = false;
     }
     int total_it = 0;
     constexpr int kMaxRestarts = 6;
@@ -736,55 +721,63 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         for (;;) {
             if (!round(r)) return;           // m = M^{-1} r, an = C m
             if (!dots()) return;             // (r,m), (an,m), (r,r)
-            bool conv = true;
             const bool can = total_it < A.maxiter;
-#pragma unroll
-            for (int c = 0; c < KG; ++c) {
-                const double g = S.sums[c], d = S.sums[KG + c];
-                rr[c] = S.sums[2 * KG + c];
+            if (t < KG) {
+                const double g = S.sums[t], d = S.sums[KG + t];
+                my_rr = S.sums[2 * KG + t];
                 if (!have_bb) {
-                    bb[c] = rr[c];
-                    done[c] = (c >= k) || !(bb[c] > 0.0);
+                    my_bb = my_rr;
+                    my_done = (t >= k) || !(my_bb > 0.0);
                 }
                 double al = 0.0, be = 0.0;
-                if (!done[c] && rr[c] > rtol2 * bb[c]) {
-                    conv = false;
-                    if (!can) {
-                    } else if (first) {
-                        al = g / d;
-                    } else {
-                        be = g / gam[c];
-                        al = g / (d - be * g / alpha[c]);
+                const bool live = !my_done && my_rr > rtol2 * my_bb;
+                if (live) {
+                    if (can) {
+                        if (first) {
+                            al = g / d;
+                        } else {
+                            be = g / my_gam;
+                            al = g / (d - be * g / my_alpha);
+                        }
+                        my_its = total_it + 1;
                     }
-                    gam[c] = g;
-                    alpha[c] = al;
+                    my_gam = g;
+                    my_alpha = al;
                 }
-                // columns that converged (or are done) keep al = 0: x and r stay
+                S.coef[t] = al;
+                S.coef[KG + t] = be;
+                S.live[t] = live ? 1 : 0;
+            }
+            have_bb = true;
+            __syncthreads();
+            bool conv = true;
+#pragma unroll
+            for (int c = 0; c < KG; ++c) {
+                // columns that converged (or are done) have alpha = 0: x and r stay
+                const double al = S.coef[c], be = S.coef[KG + c];
+                conv = conv && S.live[c] == 0;
                 p[c] = m[c] + be * p[c];
                 s[c] = an[c] + be * s[c];
                 x[c] += al * p[c];
                 r[c] -= al * s[c];
             }
-            have_bb = true;
-            __syncthreads();
             if (conv || !can) break;
             ++total_it;
-#pragma unroll
-            for (int c = 0; c < KG; ++c)
-                if (!done[c] && rr[c] > rtol2 * bb[c]) its[c] = total_it;
             first = false;
         }
         // ---- verify: recompute the true residual, restart from it if needed
         if (!true_residual()) return;
+        if (t < KG) {
+            if (!my_done) {
+                my_rr = S.sums[t];
+                if (my_rr <= rtol2 * my_bb) my_done = true;
+            }
+            S.live[t] = my_done ? 0 : 1;
+        }
+        __syncthreads();
         bool all = true;
 #pragma unroll
-        for (int c = 0; c < KG; ++c) {
-            if (!done[c]) {
-                rr[c] = S.sums[c];
-                if (rr[c] <= rtol2 * bb[c]) done[c] = true;
-            }
-            all = all && done[c];
-        }
+        for (int c = 0; c < KG; ++c) all = all && S.live[c] == 0;
         __syncthreads();
         if (all || total_it >= A.maxiter) break;
     }
@@ -793,8 +786,8 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         for (int c = 0; c < KG; ++c)
             if (c < k) A.x[i * k + c] = x[c];
     if (B == 0 && t < k) {
-        A.iters[t] = its[t];
-        A.relres[t] = bb[t] > 0.0 ? sqrt(rr[t] / bb[t]) : 0.0;
+        A.iters[t] = my_its;
+        A.relres[t] = my_bb > 0.0 ? sqrt(my_rr / my_bb) : 0.0;
     }
 }
 
