@@ -147,6 +147,20 @@ def cpu_baseline(mesh, u, target_s: float):
     }
 
 
+def pcg_report(n: int, k: int, cg_ms, iters) -> dict:
+    """The preconditioned CG launches, the largest share of the step: time per iteration and
+    the algorithmic HBM bytes of one iteration (the block solves written and read once,
+    8 n k each; block sums and partial dot products, 64 nb k), against the HBM peak."""
+    nb = -(-n // 128)
+    it = max(1, sum(iters))
+    us = 1e3 * sum(cg_ms) / it
+    bytes_it = 16.0 * n * k + 64.0 * nb * k
+    gbs = bytes_it / (us * 1e-6) / 1e9
+    return {"bound": "grid-barrier latency (two grid-wide exchanges per iteration)",
+            "us_per_iteration": us, "hbm_bytes_per_iteration": bytes_it, "achieved_GBs": gbs,
+            "peak_GBs": PEAK_HBM_GBS, "frac_hbm": gbs / PEAK_HBM_GBS}
+
+
 def _timed(fn, reps=3):
     import torch
     fn()
@@ -428,6 +442,7 @@ def main():
             },
             "cg_ms": {"solve1": cg_ms[0], "solve2": cg_ms[1]},
             "cg_iters": [int(reps[-1].cg_iters[0]), int(reps[-1].cg_iters[1])],
+            "pcg": pcg_report(mesh.nV, 3, cg_ms, [int(reps[-1].cg_iters[0]), int(reps[-1].cg_iters[1])]),
         },
         "energy": E,
     }
