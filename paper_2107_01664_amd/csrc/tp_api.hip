@@ -230,11 +230,11 @@ struct tp_problem {
     // two-level Schwarz preconditioner (block order, dense block inverses, coarse inverse)
     bool have_pcg = false;
     PcgSetup pcg;
-    DevBuf<int32_t> pcg_perm, pcg_pcol, pcg_bstart, pcg_badj_off, pcg_badj, pcg_whole, pcg_blk,
-        pcg_bcomp, pcg_ncb;
-    DevBuf<uint8_t> pcg_pslot;
+    DevBuf<int32_t> pcg_perm, pcg_pcol, pcg_bstart, pcg_whole, pcg_blk, pcg_astart, pcg_aob, pcg_acomp,
+        pcg_abl_off, pcg_abl;
+    DevBuf<int8_t> pcg_rslot, pcg_eslot;
     DevBuf<float> pcg_Binv;
-    DevBuf<double> pcg_pval, pcg_C0inv, pcg_Vb, pcg_rho, pcg_red, pcg_bp, pcg_xp;
+    DevBuf<double> pcg_pval, pcg_phi, pcg_rw, pcg_esum, pcg_C0inv, pcg_Vb, pcg_rho, pcg_red, pcg_bp, pcg_xp;
     int64_t nnz = 0;
     int ncomp = 0;
 
@@ -284,9 +284,10 @@ struct tp_problem {
         b += vf_off.bytes() + vf_idx.bytes() + tmp_i.bytes() + tmp_j.bytes() + lap_off.bytes() +
              lap_col.bytes() + comp.bytes() + lap_val.bytes() + inv_count.bytes() + ell_col.bytes() +
              ell_val.bytes();
-        b += pcg_perm.bytes() + pcg_pcol.bytes() + pcg_bstart.bytes() + pcg_badj_off.bytes() +
-             pcg_badj.bytes() + pcg_whole.bytes() + pcg_blk.bytes() + pcg_bcomp.bytes() + pcg_ncb.bytes() +
-             pcg_pslot.bytes() + pcg_Binv.bytes() + pcg_pval.bytes() + pcg_C0inv.bytes() + pcg_Vb.bytes() +
+        b += pcg_perm.bytes() + pcg_pcol.bytes() + pcg_bstart.bytes() + pcg_whole.bytes() + pcg_blk.bytes() +
+             pcg_astart.bytes() + pcg_aob.bytes() + pcg_acomp.bytes() + pcg_abl_off.bytes() + pcg_abl.bytes() +
+             pcg_rslot.bytes() + pcg_eslot.bytes() + pcg_phi.bytes() + pcg_rw.bytes() + pcg_esum.bytes() +
+             pcg_Binv.bytes() + pcg_pval.bytes() + pcg_C0inv.bytes() + pcg_Vb.bytes() +
              pcg_rho.bytes() + pcg_red.bytes() + pcg_bp.bytes() + pcg_xp.bytes();
         b += part.bytes() + gface.bytes() + zbuf.bytes() + scal.bytes() + red.bytes() + vol6.bytes() +
              edge.bytes() + ub.bytes();
@@ -495,7 +496,7 @@ tp_status build_pcg(tp_problem* P, const std::vector<int32_t>& label, int ncomp,
     std::vector<int32_t> iperm(n);
     for (int64_t i = 0; i < n; ++i) iperm[perm[i]] = (int32_t)i;
     // blocks: each component [c0, c1) in the new order cut into ceil(m / BS) equal parts
-    std::vector<int32_t> bstart, bcomp, whole, ncb(ncomp, 0);
+    std::vector<int32_t> bstart, bcomp, whole;
     int64_t pos = 0;
     while (pos < n) {
         const int c = label[perm[pos]];
@@ -507,48 +508,70 @@ tp_status build_pcg(tp_problem* P, const std::vector<int32_t>& label, int ncomp,
             bstart.push_back((int32_t)(pos + q * m / nbc));
             bcomp.push_back(c);
             whole.push_back(nbc == 1 ? 1 : 0);
-            ncb[c] += 1;
         }
         pos = end;
     }
     const int nb = (int)bstart.size();
     bstart.push_back((int32_t)n);
     P->have_pcg = false;
-    if (!pcg_supported(nb, 0)) return TP_OK;          // too many blocks: plain CG
+    if (nb < 1 || nb > pcg_max_blocks()) return TP_OK;        // too many blocks: plain CG
     std::vector<int32_t> blk(n);
     for (int b = 0; b < nb; ++b)
         for (int32_t i = bstart[b]; i < bstart[b + 1]; ++i) blk[i] = b;
-    // neighbouring blocks
-    std::vector<int32_t> badj_off(1, 0), badj;
+    // aggregates: runs of `agg` consecutive blocks of one component, so that the coarse
+    // space (4 functions per aggregate) has at most pcg_max_coarse() functions
+    const int agg = std::max(1, (4 * nb + pcg_max_coarse() - 1) / pcg_max_coarse());
+    std::vector<int32_t> astart, aob(nb), acomp;
+    for (int b = 0; b < nb;) {
+        int e = b;
+        while (e < nb && e - b < agg && bcomp[e] == bcomp[b]) ++e;
+        for (int q = b; q < e; ++q) aob[q] = (int32_t)astart.size();
+        astart.push_back(b);
+        acomp.push_back(bcomp[b]);
+        b = e;
+    }
+    const int na = (int)astart.size();
+    astart.push_back(nb);
+    if (4 * na > pcg_max_coarse()) return TP_OK;                // too many components: plain CG
+    // aggregates touching each block (through its rows' entries), and each row's slots
+    std::vector<int32_t> abl_off(1, 0), abl;
     for (int b = 0; b < nb; ++b) {
         std::vector<int32_t> lst;
         for (int32_t i = bstart[b]; i < bstart[b + 1]; ++i) {
             const int32_t old = perm[i];
-            for (int32_t q = hoff[old]; q < hoff[old + 1]; ++q) lst.push_back(blk[iperm[hcol[q]]]);
+            for (int32_t q = hoff[old]; q < hoff[old + 1]; ++q) lst.push_back(aob[blk[iperm[hcol[q]]]]);
         }
-        lst.push_back(b);
+        lst.push_back(aob[b]);
         std::sort(lst.begin(), lst.end());
         lst.erase(std::unique(lst.begin(), lst.end()), lst.end());
-        if ((int)lst.size() > pcg_max_neighbors()) return TP_OK;   // plain CG
-        badj.insert(badj.end(), lst.begin(), lst.end());
-        badj_off.push_back((int32_t)badj.size());
+        if ((int)lst.size() > pcg_max_block_aggregates()) return TP_OK;   // plain CG
+        abl.insert(abl.end(), lst.begin(), lst.end());
+        abl_off.push_back((int32_t)abl.size());
     }
-    // permuted ELL pattern and block slots
     const int w = P->ell_w;
     std::vector<int32_t> pcol((size_t)w * n);
-    std::vector<uint8_t> pslot((size_t)w * n);
+    std::vector<int8_t> rslot((size_t)kPcgRowSlots * n, (int8_t)-1), eslot((size_t)w * n);
     for (int64_t i = 0; i < n; ++i) {
         const int32_t old = perm[i];
         const int32_t b = hoff[old], len = hoff[old + 1] - b;
         const int bi = blk[i];
+        int nq = 0;
+        int sl_of_q[kPcgRowSlots];
         for (int e = 0; e < w; ++e) {
-            const int32_t j = e < len ? iperm[hcol[b + e]] : (int32_t)i;
+            const int32_t j = e < len ? iperm[hcol[b + e]] : (int32_t)i;   // padding: the row itself, value 0
             pcol[(size_t)e * n + i] = j;
-            const int bj = blk[j];
-            int sl = 0;
-            for (int q = badj_off[bi]; q < badj_off[bi + 1]; ++q)
-                if (badj[q] == bj) sl = q - badj_off[bi];
-            pslot[(size_t)e * n + i] = (uint8_t)sl;
+            const int32_t ag = aob[blk[j]];
+            int sl = -1;
+            for (int q = abl_off[bi]; q < abl_off[bi + 1]; ++q)
+                if (abl[q] == ag) sl = q - abl_off[bi];
+            int q = 0;
+            while (q < nq && sl_of_q[q] != sl) ++q;
+            if (q == nq) {
+                if (nq == kPcgRowSlots) return TP_OK;             // plain CG
+                sl_of_q[nq++] = sl;
+                rslot[(size_t)q * n + i] = (int8_t)sl;
+            }
+            eslot[(size_t)e * n + i] = (int8_t)q;
         }
     }
     auto up = [&](auto& buf, const auto& host) -> tp_status {
@@ -558,23 +581,31 @@ tp_status build_pcg(tp_problem* P, const std::vector<int32_t>& label, int ncomp,
     };
     TP_TRY(up(P->pcg_perm, perm));
     TP_TRY(up(P->pcg_pcol, pcol));
-    TP_TRY(up(P->pcg_pslot, pslot));
     TP_TRY(up(P->pcg_bstart, bstart));
-    TP_TRY(up(P->pcg_badj_off, badj_off));
-    TP_TRY(up(P->pcg_badj, badj));
     TP_TRY(up(P->pcg_whole, whole));
     TP_TRY(up(P->pcg_blk, blk));
-    TP_TRY(up(P->pcg_bcomp, bcomp));
-    TP_TRY(up(P->pcg_ncb, ncb));
+    TP_TRY(up(P->pcg_astart, astart));
+    TP_TRY(up(P->pcg_aob, aob));
+    TP_TRY(up(P->pcg_acomp, acomp));
+    TP_TRY(up(P->pcg_abl_off, abl_off));
+    TP_TRY(up(P->pcg_abl, abl));
+    TP_TRY(up(P->pcg_rslot, rslot));
+    TP_TRY(up(P->pcg_eslot, eslot));
+    const int nc = 4 * na;
     TP_TRY(P->pcg_pval.ensure((size_t)w * n, s));
+    TP_TRY(P->pcg_phi.ensure((size_t)4 * n, s));
+    TP_TRY(P->pcg_rw.ensure((size_t)kPcgRowSlots * 4 * n, s));
+    TP_TRY(P->pcg_esum.ensure((size_t)nc, s));
     TP_TRY(P->pcg_Binv.ensure((size_t)nb * BS * BS, s));
-    TP_TRY(P->pcg_C0inv.ensure((size_t)nb * nb + nb, s));   // + per-block diagonal sums
+    TP_TRY(P->pcg_C0inv.ensure((size_t)nc * nc, s));
     TP_HIP(hipStreamSynchronize(s));
     PcgSetup& ps = P->pcg;
-    ps.n = n; ps.nb = nb; ps.ell_w = w;
-    ps.perm = P->pcg_perm.p; ps.pcol = P->pcg_pcol.p; ps.pval = P->pcg_pval.p; ps.pslot = P->pcg_pslot.p;
-    ps.bstart = P->pcg_bstart.p; ps.badj_off = P->pcg_badj_off.p; ps.badj = P->pcg_badj.p;
-    ps.whole = P->pcg_whole.p; ps.blk = P->pcg_blk.p; ps.bcomp = P->pcg_bcomp.p; ps.ncomp_blocks = P->pcg_ncb.p;
+    ps.n = n; ps.nb = nb; ps.na = na; ps.nc = nc; ps.ell_w = w;
+    ps.perm = P->pcg_perm.p; ps.pcol = P->pcg_pcol.p; ps.pval = P->pcg_pval.p;
+    ps.bstart = P->pcg_bstart.p; ps.whole = P->pcg_whole.p; ps.blk = P->pcg_blk.p;
+    ps.astart = P->pcg_astart.p; ps.agg_of_block = P->pcg_aob.p; ps.acomp = P->pcg_acomp.p;
+    ps.abl_off = P->pcg_abl_off.p; ps.abl = P->pcg_abl.p; ps.rslot = P->pcg_rslot.p; ps.eslot = P->pcg_eslot.p;
+    ps.phi = P->pcg_phi.p; ps.rw = P->pcg_rw.p; ps.esum = P->pcg_esum.p;
     ps.Binv = P->pcg_Binv.p; ps.C0inv = P->pcg_C0inv.p;
     P->have_pcg = true;
     return TP_OK;
@@ -658,7 +689,7 @@ tp_status ensure_cotan(tp_problem* P)
                                    P->lap_col.p, P->lap_val.p, P->stream));
         TP_HIP(launch_csr_to_ell(P->nV, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->ell_w,
                                  P->ell_col.p, P->ell_val.p, P->stream));
-        if (P->have_pcg) TP_HIP(launch_pcg_setup(P->pcg, P->lap_off.p, P->lap_val.p, P->stream));
+        if (P->have_pcg) TP_HIP(launch_pcg_setup(P->pcg, P->V.p, P->lap_off.p, P->lap_val.p, P->stream));
         P->cotan_valid = true;
     }
     return TP_OK;
@@ -1015,7 +1046,7 @@ tp_status ensure_cg(tp_problem* P, int k)
         const size_t n = (size_t)P->nV;
         const size_t kc = (size_t)std::min(k, kMaxGroupCols);
         TP_TRY(P->pcg_Vb.ensure(2 * n * kc, s));
-        TP_TRY(P->pcg_rho.ensure((size_t)2 * P->pcg.nb * kc, s));
+        TP_TRY(P->pcg_rho.ensure((size_t)2 * P->pcg.nb * 4 * kc, s));
         TP_TRY(P->pcg_red.ensure((size_t)2 * P->pcg.nb * 3 * kc, s));
         TP_TRY(P->pcg_bp.ensure(n * kc, s));
         TP_TRY(P->pcg_xp.ensure(n * kc, s));
@@ -1729,11 +1760,15 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
     // preconditioner
     if (prm.cg_precond) {
         const double nb = std::ceil(n / pcg_block_size()) + ncomp;
-        if (nb <= 256) {
-            const double bs = pcg_block_size();
-            b += 4 * n + 13 * n * w + 4 * 2 * (nb + 1) + 4 * nb * pcg_max_neighbors() + 8 * nb + 4 * n +
-                 4 * ncomp + 4 * nb * bs * bs + 8 * nb * nb;
-            b += 4 * 8 * n * kMaxGroupCols + 8 * 2 * nb * kMaxGroupCols + 8 * 6 * nb * kMaxGroupCols;
+        if (nb <= pcg_max_blocks()) {
+            const double bs = pcg_block_size(), ncmax = pcg_max_coarse();
+            // permutation, ELL pattern / values / entry slots, block and aggregate tables,
+            // row slots, coarse functions and row weights, block inverses, coarse inverse
+            b += 4 * n + 13 * n * w + 4 * 2 * (nb + 1) + 4 * nb * (4 + pcg_max_block_aggregates()) + 4 * n +
+                 (4 + 32 + 8 * 4 * kPcgRowSlots) * n + 8 * ncmax + 4 * nb * bs * bs + 8 * ncmax * ncmax;
+            // solve work: two copies of the block solves, block shares of the coarse
+            // right-hand side and partial sums, permuted b and x
+            b += 8.0 * n * kMaxGroupCols * 4 + 8 * 2 * nb * 4 * kMaxGroupCols + 8 * 6 * nb * kMaxGroupCols;
         }
     }
     // CG state and reductions

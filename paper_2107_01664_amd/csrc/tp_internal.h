@@ -220,24 +220,36 @@ hipError_t launch_cg(int64_t n, const int32_t* ecol, const double* eval, int ell
                      const CgWork& w, hipStream_t s);
 
 // Two-level additive Schwarz preconditioned CG (blocks of pcg_block_size() vertices in
-// (component, Morton) order, dense block inverses in LDS, Galerkin coarse correction).
+// (component, Morton) order, dense block inverses in LDS; Galerkin coarse correction on
+// aggregates of consecutive blocks with four coarse functions each: an orthonormal basis of
+// {1, x, y, z} on the aggregate's vertices).
+constexpr int kPcgRowSlots = 4;          // neighbouring aggregates of one row, at most
 struct PcgSetup {
     int64_t n = 0;
     int nb = 0;
+    int na = 0;                           // aggregates
+    int nc = 0;                           // coarse functions (4 per aggregate)
     int ell_w = 0;
     const int32_t* perm = nullptr;        // [n] block order -> vertex
     const int32_t* pcol = nullptr;        // [ell_w][n] permuted ELL columns
     double* pval = nullptr;               // [ell_w][n] permuted ELL values (per geometry)
-    const uint8_t* pslot = nullptr;       // [ell_w][n]
     const int32_t* bstart = nullptr;      // [nb + 1]
-    const int32_t* badj_off = nullptr;    // [nb + 1]
-    const int32_t* badj = nullptr;
     const int32_t* whole = nullptr;       // [nb] block is a whole component
     const int32_t* blk = nullptr;         // [n] block of each (permuted) row
-    const int32_t* bcomp = nullptr;       // [nb] component of each block
-    const int32_t* ncomp_blocks = nullptr;// [ncomp] blocks per component
+    const int32_t* astart = nullptr;      // [na + 1] first block of each aggregate
+    const int32_t* agg_of_block = nullptr;// [nb]
+    const int32_t* acomp = nullptr;       // [na] component of each aggregate
+    const int32_t* abl_off = nullptr;     // [nb + 1] aggregates touching each block
+    const int32_t* abl = nullptr;         //          (sorted, the block's own included)
+    const int8_t* rslot = nullptr;        // [kPcgRowSlots][n] slots (in the block's list) of the
+                                          // aggregates a row touches, -1 when unused
+    const int8_t* eslot = nullptr;        // [ell_w][n] row slot of each ELL entry
+    double* phi = nullptr;                // [n][4] coarse functions at each row (per geometry)
+    double* rw = nullptr;                 // [kPcgRowSlots][4][n] sum over a row's entries of one
+                                          // aggregate of C_ij phi_j (per geometry)
+    double* esum = nullptr;               // [nc] sum of each coarse function (per geometry)
     float* Binv = nullptr;                // [nb][bs][bs], FP32
-    double* C0inv = nullptr;              // [nb][nb], then nb doubles of set-up scratch
+    double* C0inv = nullptr;              // [nc][nc] (the coarse matrix, then its inverse)
 };
 struct PcgWork {
     double* Vb = nullptr;       // 2 * n * k   (two copies, see the kernel)
@@ -249,9 +261,13 @@ struct PcgWork {
     int* flags = nullptr;
 };
 int pcg_block_size();
-int pcg_max_neighbors();
-bool pcg_supported(int64_t nb, int ncomp_blocks_max);
-hipError_t launch_pcg_setup(const PcgSetup& ps, const int32_t* lap_off, const double* lap_val, hipStream_t s);
+int pcg_max_blocks();                    // blocks of one problem, at most
+int pcg_max_coarse();                    // coarse functions of one problem, at most
+int pcg_max_block_aggregates();          // aggregates touching one block, at most
+// Per-geometry set-up: permuted matrix values, block inverses, coarse functions, the
+// coarse matrix and its inverse.  V: vertices (n x 3, caller order).
+hipError_t launch_pcg_setup(const PcgSetup& ps, const double* V, const int32_t* lap_off, const double* lap_val,
+                            hipStream_t s);
 hipError_t launch_permute_rows(int64_t n, int k, const int32_t* perm, int ld, int c0, const double* src,
                                double* dst, bool forward, hipStream_t s);
 // One system of a multi-problem solve: b, x in block order, [n][k].

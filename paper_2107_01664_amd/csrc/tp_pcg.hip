@@ -38,7 +38,7 @@ namespace tp {
 
 constexpr int kBS = 128;            // vertices per block = row-owning threads of a solver workgroup
 constexpr int kThreads = 2 * kBS;   // threads per solver workgroup: row owners + helpers
-constexpr int kMaxNbn = 32;         // neighbouring blocks of a block (itself included)
+constexpr int kMaxAggNbn = 16;      // aggregates touching a block (its own included)
 constexpr int kMaxNbPcg = 256;      // blocks (one co-resident workgroup per block)
 static_assert(kMaxNbPcg <= kMaxBarrierW, "one barrier flag per block");
 
@@ -125,102 +125,275 @@ __global__ __launch_bounds__(kInvThreads) void k_block_inverse(int64_t n, int w,
     }
 }
 
-// Coarse matrix rows: C0[B][B'] = sum over rows of B of the entries in columns of B', and
-// bdiag[B] = sum of the diagonal entries of C over the rows of B.  One workgroup per block;
-// thread 0 adds in row order (deterministic).
-__global__ __launch_bounds__(64) void k_coarse_rows(int64_t n, int w, int nb, const int32_t* __restrict__ pcol,
-                                                    const double* __restrict__ pval,
-                                                    const int32_t* __restrict__ bstart,
-                                                    const int32_t* __restrict__ blk,
-                                                    double* __restrict__ C0, double* __restrict__ bdiag)
+// ---- coarse space: per aggregate, an orthonormal basis (in the Euclidean product on the
+// aggregate's vertices) of {1, x, y, z}, with x, y, z centred and scaled on the aggregate.
+// It is the Cholesky factor L of the 4 x 4 Gram matrix that orthonormalises: phi = V L^-T.
+// A function whose remainder after the previous ones is below 1e-6 of its norm (a flat or
+// tiny aggregate) is dropped: its values are zero and its coarse row and column are zero
+// but for a unit diagonal.
+
+constexpr int kAggThreads = 256;
+
+// Fixed-order sum of M values per thread over a kAggThreads workgroup.
+template <int M>
+__device__ __forceinline__ void agg_sum(const double (&v)[M], double* sh, double* out)
 {
-    extern __shared__ __align__(16) double acc[];   // nb
-    const int B = blockIdx.x;
-    for (int t = threadIdx.x; t < nb; t += blockDim.x) acc[t] = 0.0;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double dg = 0.0;
-        for (int64_t i = bstart[B]; i < bstart[B + 1]; ++i)
-            for (int e = 0; e < w; ++e) {
-                const int32_t j = pcol[(int64_t)e * n + i];
-                const double a = pval[(int64_t)e * n + i];
-                acc[blk[j]] += a;
-                if (j == i) dg += a;      // padding entries point at i with value 0
-            }
-        bdiag[B] = dg;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < M; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) sh[wave * M + q] = s;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < nb; t += blockDim.x) C0[(int64_t)B * nb + t] = acc[t];
-}
-
-// Inverse of the nb x nb coarse matrix after adding the per-component rank-one terms.  The
-// rank-one scale of a component of several blocks is the mean diagonal of the coarse matrix
-// over such blocks; a component of one block has a zero coarse entry (C is singular on its
-// constants), so it gets the block's own diagonal sum of C instead (any positive scale gives
-// the same action on mean-zero vectors; this one keeps rounding errors of the block sums from
-// being amplified).  The matrix is symmetric positive definite, so no pivoting is needed.
-constexpr int kCoarseThreads = 1024;
-constexpr int kCoarseSweepMax = 200;   // packed upper triangle: 200 x 201 / 2 doubles = 157 KB of LDS
-
-__device__ __forceinline__ double coarse_entry(const double* __restrict__ G, int nb, int i, int j,
-                                               const int32_t* __restrict__ bcomp,
-                                               const int32_t* __restrict__ ncomp_blocks,
-                                               const double* __restrict__ bdiag, double dmean)
-{
-    // the block sums of the two triangles may differ in the last bit: their mean is used
-    double v = 0.5 * (G[(int64_t)i * nb + j] + G[(int64_t)j * nb + i]);
-    if (bcomp[i] == bcomp[j]) {
-        const int nc = ncomp_blocks[bcomp[i]];
-        v += nc > 1 ? dmean / nc : bdiag[i];
+    if ((int)threadIdx.x < M) {
+        double a = 0.0;
+        for (int w = 0; w < kAggThreads / 64; ++w) a += sh[w * M + threadIdx.x];
+        out[threadIdx.x] = a;
     }
-    return v;
+    __syncthreads();
 }
 
-__device__ double coarse_dmean(const double* __restrict__ G, int nb, const int32_t* __restrict__ bcomp,
-                               const int32_t* __restrict__ ncomp_blocks)
+// One workgroup per aggregate: phi[i][0..4) for its rows (block order) and esum[4g + a].
+__global__ __launch_bounds__(kAggThreads) void k_agg_basis(const int32_t* __restrict__ perm,
+                                                             const double* __restrict__ V,
+                                                             const int32_t* __restrict__ astart,
+                                                             const int32_t* __restrict__ bstart,
+                                                             double* __restrict__ phi, double* __restrict__ esum)
 {
-    double s = 0.0;
-    int cnt = 0;
-    for (int i = 0; i < nb; ++i)
-        if (ncomp_blocks[bcomp[i]] > 1) {
-            s += G[(int64_t)i * nb + i];
-            ++cnt;
+    __shared__ double sh[(kAggThreads / 64) * 10];
+    __shared__ double tot[10];
+    __shared__ double T[16];
+    const int g = blockIdx.x;
+    const int v0 = bstart[astart[g]], v1 = bstart[astart[g + 1]];
+    const double m = (double)(v1 - v0);
+    // centroid
+    double ps[3] = {0.0, 0.0, 0.0};
+    for (int i = v0 + (int)threadIdx.x; i < v1; i += kAggThreads) {
+        const int64_t o = (int64_t)perm[i] * 3;
+        ps[0] += V[o]; ps[1] += V[o + 1]; ps[2] += V[o + 2];
+    }
+    agg_sum<3>(ps, sh, tot);
+    const double cx = tot[0] / m, cy = tot[1] / m, cz = tot[2] / m;
+    __syncthreads();
+    // scale: largest coordinate offset (a maximum does not depend on the order)
+    double pm[1] = {0.0};
+    for (int i = v0 + (int)threadIdx.x; i < v1; i += kAggThreads) {
+        const int64_t o = (int64_t)perm[i] * 3;
+        pm[0] = fmax(pm[0], fmax(fabs(V[o] - cx), fmax(fabs(V[o + 1] - cy), fabs(V[o + 2] - cz))));
+    }
+    {
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        double w = pm[0];
+        for (int off = 32; off > 0; off >>= 1) w = fmax(w, __shfl_xor(w, off));
+        if (lane == 0) sh[wave] = w;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double a = 0.0;
+            for (int q = 0; q < kAggThreads / 64; ++q) a = fmax(a, sh[q]);
+            tot[0] = a > 0.0 ? 1.0 / a : 1.0;
         }
-    return cnt > 0 ? s / cnt : 0.0;
+        __syncthreads();
+    }
+    const double is = tot[0];
+    __syncthreads();
+    // Gram matrix of (1, x', y', z'): entries (0,0) (0,1) (0,2) (0,3) (1,1) (1,2) (1,3) (2,2) (2,3) (3,3)
+    double gs[10];
+#pragma unroll
+    for (int q = 0; q < 10; ++q) gs[q] = 0.0;
+    for (int i = v0 + (int)threadIdx.x; i < v1; i += kAggThreads) {
+        const int64_t o = (int64_t)perm[i] * 3;
+        const double f[4] = {1.0, (V[o] - cx) * is, (V[o + 1] - cy) * is, (V[o + 2] - cz) * is};
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = a; b < 4; ++b) gs[q++] += f[a] * f[b];
+    }
+    agg_sum<10>(gs, sh, tot);
+    if (threadIdx.x == 0) {
+        double G[4][4];
+        int q = 0;
+        for (int a = 0; a < 4; ++a)
+            for (int b = a; b < 4; ++b) G[a][b] = G[b][a] = tot[q++];
+        // Cholesky with dropped pivots, then T = L^{-1} (rows of dropped functions zero)
+        double L[4][4] = {};
+        bool keep[4];
+        for (int a = 0; a < 4; ++a) {
+            double d = G[a][a];
+            for (int c = 0; c < a; ++c) d -= L[a][c] * L[a][c];
+            keep[a] = d > 1e-12 * G[a][a] && G[a][a] > 0.0;
+            const double la = keep[a] ? sqrt(d) : 0.0;
+            L[a][a] = la;
+            for (int b = a + 1; b < 4; ++b) {
+                double v = G[b][a];
+                for (int c = 0; c < a; ++c) v -= L[b][c] * L[a][c];
+                L[b][a] = keep[a] ? v / la : 0.0;
+            }
+        }
+        double Ti[4][4] = {};
+        for (int a = 0; a < 4; ++a) {
+            if (!keep[a]) continue;
+            Ti[a][a] = 1.0 / L[a][a];
+            for (int b = 0; b < a; ++b) {
+                double v = 0.0;
+                for (int c = b; c < a; ++c) v += L[a][c] * Ti[c][b];
+                Ti[a][b] = -v / L[a][a];
+            }
+        }
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) T[a * 4 + b] = Ti[a][b];
+    }
+    __syncthreads();
+    double es[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = v0 + (int)threadIdx.x; i < v1; i += kAggThreads) {
+        const int64_t o = (int64_t)perm[i] * 3;
+        const double f[4] = {1.0, (V[o] - cx) * is, (V[o + 1] - cy) * is, (V[o + 2] - cz) * is};
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            double v = 0.0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) v += T[a * 4 + b] * f[b];
+            phi[(int64_t)i * 4 + a] = v;
+            es[a] += v;
+        }
+    }
+    agg_sum<4>(es, sh, tot);
+    if (threadIdx.x < 4) esum[4 * g + threadIdx.x] = tot[threadIdx.x];
 }
 
-// nb <= kCoarseSweepMax: symmetric sweeps in LDS on the packed upper triangle (row i holds
-// columns i .. nb-1).  Sweeping pivot k with d = a_kk maps a_ij -> a_ij - a_ik a_kj / d
+// Per row i and slot q (an aggregate the row's entries reach): rw[q][a][i] = sum over the
+// entries j of that aggregate of C_ij phi_j[a], added in ELL order.
+__global__ void k_row_coarse(int64_t n, int w, const int32_t* __restrict__ pcol, const double* __restrict__ pval,
+                             const int8_t* __restrict__ eslot, const double* __restrict__ phi, double* __restrict__ rw)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc[kPcgRowSlots][4];
+#pragma unroll
+    for (int q = 0; q < kPcgRowSlots; ++q)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) acc[q][a] = 0.0;
+    for (int e = 0; e < w; ++e) {
+        const int32_t j = pcol[(int64_t)e * n + i];
+        const double c = pval[(int64_t)e * n + i];
+        const int q = eslot[(int64_t)e * n + i];
+#pragma unroll
+        for (int qq = 0; qq < kPcgRowSlots; ++qq)
+            if (qq == q)
+#pragma unroll
+                for (int a = 0; a < 4; ++a) acc[qq][a] += c * phi[(int64_t)j * 4 + a];
+    }
+#pragma unroll
+    for (int q = 0; q < kPcgRowSlots; ++q)
+#pragma unroll
+        for (int a = 0; a < 4; ++a) rw[((int64_t)q * 4 + a) * n + i] = acc[q][a];
+}
+
+// Galerkin coarse matrix rows of aggregate g: C0[4g + a][4h + b] = sum over rows i of g of
+// phi_i[a] rw[q(h)][b][i].  kAggThreads threads = 16 row groups x 16 (a, b) pairs; each group
+// adds a contiguous share of the rows, the groups are added in order.
+constexpr int kAsmGroups = kAggThreads / 16;
+__global__ __launch_bounds__(kAggThreads) void k_coarse_assemble(int64_t n, int na, int nc,
+                                                                   const int32_t* __restrict__ astart,
+                                                                   const int32_t* __restrict__ bstart,
+                                                                   const int32_t* __restrict__ blk,
+                                                                   const int32_t* __restrict__ abl_off,
+                                                                   const int32_t* __restrict__ abl,
+                                                                   const int8_t* __restrict__ rslot,
+                                                                   const double* __restrict__ phi,
+                                                                   const double* __restrict__ rw,
+                                                                   double* __restrict__ C0)
+{
+    extern __shared__ __align__(16) double acc[];   // [kAsmGroups][na][16]
+    const int g = blockIdx.x;
+    const int v0 = bstart[astart[g]], v1 = bstart[astart[g + 1]];
+    for (int t = threadIdx.x; t < kAsmGroups * na * 16; t += kAggThreads) acc[t] = 0.0;
+    __syncthreads();
+    const int grp = threadIdx.x / 16, ab = threadIdx.x % 16, a = ab / 4, b = ab % 4;
+    const int rows = v1 - v0, chunk = (rows + kAsmGroups - 1) / kAsmGroups;
+    const int r0 = v0 + grp * chunk, r1 = min(v1, r0 + chunk);
+    double* my = acc + (int64_t)grp * na * 16;
+    for (int i = r0; i < r1; ++i) {
+        const int B = blk[i];
+        const double pa = phi[(int64_t)i * 4 + a];
+#pragma unroll
+        for (int q = 0; q < kPcgRowSlots; ++q) {
+            const int sl = rslot[(int64_t)q * n + i];
+            if (sl < 0) continue;
+            const int h = abl[abl_off[B] + sl];
+            my[h * 16 + ab] += pa * rw[((int64_t)q * 4 + b) * n + i];
+        }
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < na * 16; t += kAggThreads) {
+        double v = 0.0;
+        for (int q = 0; q < kAsmGroups; ++q) v += acc[(int64_t)q * na * 16 + t];
+        const int h = t / 16, aa = (t % 16) / 4, bb = t % 4;
+        C0[(int64_t)(4 * g + aa) * nc + 4 * h + bb] = v;
+    }
+}
+
+// Inverse of the nc x nc coarse matrix (nc <= kCoarseMax) after the regularisation of each
+// component's constants: with e the coefficients of the component's constant function in the
+// coarse basis (e_d = sum of coarse function d), the term dmean e e^T / (e^T e) is added,
+// dmean the mean of the kept diagonal entries; the action on per-component mean-zero vectors
+// is that of the pseudo-inverse.  The matrix is symmetric positive definite, so no pivoting
+// is needed.
+constexpr int kCoarseThreads = 1024;
+constexpr int kCoarseMax = 200;   // packed upper triangle: 200 x 201 / 2 doubles = 157 KB of LDS
+constexpr int kMaxCoarseComp = kCoarseMax / 4;
+
+// nc <= kCoarseMax: symmetric sweeps in LDS on the packed upper triangle (row i holds
+// columns i .. nc-1).  Sweeping pivot k with d = a_kk maps a_ij -> a_ij - a_ik a_kj / d
 // (i, j != k), a_ik -> a_ik / d, a_kk -> -1 / d; after all pivots the matrix is -A^{-1}.
 // Rows are spread over the waves, columns over the lanes.
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse_sweep(int nb, const int32_t* __restrict__ bcomp,
-                                                                 const int32_t* __restrict__ ncomp_blocks,
-                                                                 const double* __restrict__ bdiag,
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_sweep(int nc, const int32_t* __restrict__ acomp,
+                                                                 const double* __restrict__ esum,
                                                                  double* __restrict__ G)
 {
     extern __shared__ __align__(16) double A[];
-    __shared__ double fcol[kMaxNbPcg];
+    __shared__ double fcol[kCoarseMax];
     __shared__ double dmean_sh;
+    __shared__ double enorm[kMaxCoarseComp];   // e^T e per component, indexed by first aggregate's slot
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     constexpr int kWaves = kCoarseThreads / 64;
-    auto off = [&](int i) { return i * nb - (i * (i - 1)) / 2; };
-    if (threadIdx.x == 0) dmean_sh = coarse_dmean(G, nb, bcomp, ncomp_blocks);
+    auto off = [&](int i) { return i * nc - (i * (i - 1)) / 2; };
+    if (threadIdx.x == 0) {
+        double sd = 0.0;
+        int cnt = 0;
+        for (int i = 0; i < nc; ++i)
+            if (G[(int64_t)i * nc + i] > 0.0) {
+                sd += G[(int64_t)i * nc + i];
+                ++cnt;
+            }
+        dmean_sh = cnt > 0 ? sd / cnt : 1.0;
+        for (int q = 0; q < kMaxCoarseComp; ++q) enorm[q] = 0.0;
+        // components are numbered densely over the aggregates (acomp < nc / 4)
+        for (int i = 0; i < nc; ++i) enorm[acomp[i / 4]] += esum[i] * esum[i];
+    }
     __syncthreads();
     const double dmean = dmean_sh;
-    for (int i = wave; i < nb; i += kWaves)
-        for (int j = i + lane; j < nb; j += 64) A[off(i) + j - i] = coarse_entry(G, nb, i, j, bcomp, ncomp_blocks, bdiag, dmean);
+    for (int i = wave; i < nc; i += kWaves)
+        for (int j = i + lane; j < nc; j += 64) {
+            // the two triangles are assembled by different aggregates: their mean is used
+            double v = 0.5 * (G[(int64_t)i * nc + j] + G[(int64_t)j * nc + i]);
+            const int ci = acomp[i / 4];
+            if (ci == acomp[j / 4] && enorm[ci] > 0.0) v += dmean * esum[i] * esum[j] / enorm[ci];
+            if (i == j && !(G[(int64_t)i * nc + i] > 0.0)) v = 1.0;   // dropped coarse function
+            A[off(i) + j - i] = v;
+        }
     __syncthreads();
-    for (int k = 0; k < nb; ++k) {
+    for (int k = 0; k < nc; ++k) {
         const double d = A[off(k)];
-        if ((int)threadIdx.x < nb) {
+        if ((int)threadIdx.x < nc) {
             const int i = threadIdx.x;
             fcol[i] = i <= k ? A[off(i) + k - i] : A[off(k) + i - k];
         }
         __syncthreads();
         const double invd = 1.0 / d;
-        for (int i = wave; i < nb; i += kWaves) {
+        for (int i = wave; i < nc; i += kWaves) {
             const double fi = fcol[i];
-            for (int j = i + lane; j < nb; j += 64) {
+            for (int j = i + lane; j < nc; j += 64) {
                 const int idx = off(i) + j - i;
                 double v;
                 if (i == k && j == k) v = -invd;
@@ -232,64 +405,18 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_sweep(int nb, const i
         }
         __syncthreads();
     }
-    for (int i = wave; i < nb; i += kWaves)
-        for (int j = i + lane; j < nb; j += 64) {
+    for (int i = wave; i < nc; i += kWaves)
+        for (int j = i + lane; j < nc; j += 64) {
             const double v = -A[off(i) + j - i];
-            G[(int64_t)i * nb + j] = v;
-            G[(int64_t)j * nb + i] = v;
+            G[(int64_t)i * nc + j] = v;
+            G[(int64_t)j * nc + i] = v;
         }
 }
 
-// nb > kCoarseSweepMax: Gauss-Jordan elimination on the full matrix in global memory.
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(int nb, const int32_t* __restrict__ bcomp,
-                                                                   const int32_t* __restrict__ ncomp_blocks,
-                                                                   const double* __restrict__ bdiag,
-                                                                   double* __restrict__ G)
+__global__ void k_fill_zero(double* __restrict__ p, int64_t n)
 {
-    __shared__ double fcol[kMaxNbPcg];
-    __shared__ double dmean_sh;
-    const int nn = nb * nb;
-    if (threadIdx.x == 0) dmean_sh = coarse_dmean(G, nb, bcomp, ncomp_blocks);
-    __syncthreads();
-    const double dmean = dmean_sh;
-    // symmetrised entries with the rank-one terms: the upper triangle first (each pair read
-    // and written by one thread), then the diagonal and the mirrored lower triangle
-    double* A = G;
-    {
-        for (int t = threadIdx.x; t < nn; t += kCoarseThreads) {
-            const int i = t / nb, j = t - i * nb;
-            if (i < j) A[t] = coarse_entry(G, nb, i, j, bcomp, ncomp_blocks, bdiag, dmean);
-        }
-        __threadfence_block();
-        __syncthreads();
-        for (int t = threadIdx.x; t < nn; t += kCoarseThreads) {
-            const int i = t / nb, j = t - i * nb;
-            if (i == j) A[t] += ncomp_blocks[bcomp[i]] > 1 ? dmean / ncomp_blocks[bcomp[i]] : bdiag[i];
-            else if (i > j) A[t] = A[(int64_t)j * nb + i];
-        }
-        __threadfence_block();
-        __syncthreads();
-    }
-    for (int k = 0; k < nb; ++k) {
-        const double p = 1.0 / A[(int64_t)k * nb + k];
-        __syncthreads();
-        for (int j = threadIdx.x; j < nb; j += kCoarseThreads) fcol[j] = A[(int64_t)j * nb + k];
-        __syncthreads();
-        for (int j = threadIdx.x; j < nb; j += kCoarseThreads)
-            A[(int64_t)k * nb + j] = (j == k ? 1.0 : A[(int64_t)k * nb + j]) * p;
-        __threadfence_block();
-        __syncthreads();
-#pragma unroll 8
-        for (int t = threadIdx.x; t < nn; t += kCoarseThreads) {
-            const int i = t / nb, j = t - i * nb;
-            if (i != k) {
-                const double base = (j == k) ? 0.0 : A[t];
-                A[t] = base - fcol[i] * A[(int64_t)k * nb + j];
-            }
-        }
-        __threadfence_block();
-        __syncthreads();
-    }
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) p[t] = 0.0;
 }
 
 // forward: dst[i][c] = src[perm[i]][c0 + c] (dst in block order, row stride k);
@@ -310,19 +437,24 @@ __global__ void k_permute_rows(int64_t n, int k, const int32_t* __restrict__ per
 struct PcgArgs {
     int64_t n;
     int nb;
+    int nc;                   // coarse functions (4 per aggregate)
     int ell_w;
     const int32_t* pcol;      // [ell_w][n]
     const double* pval;       // [ell_w][n]
-    const uint8_t* pslot;     // [ell_w][n] slot of the column's block in the row block's list
     const int32_t* bstart;    // [nb + 1]
-    const int32_t* badj_off;  // [nb + 1]
-    const int32_t* badj;      // neighbour blocks (sorted, itself included)
+    const int32_t* astart;    // [na + 1] first block of each aggregate
+    const int32_t* agg_of_block;
+    const int32_t* abl_off;   // [nb + 1] aggregates touching each block (sorted, own included)
+    const int32_t* abl;
+    const int8_t* rslot;      // [kPcgRowSlots][n]
+    const double* phi;        // [n][4]
+    const double* rw;         // [kPcgRowSlots][4][n]
     const float* Binv;        // [nb][kBS][kBS], FP32
-    const double* C0inv;      // [nb][nb]
+    const double* C0inv;      // [nc][nc]
     const double* b;          // [n][k] (block order)
     double* x;                // [n][k]
     double* Vb;               // [2][n][k] block solves, copy = barrier count % 2
-    double* rho;              // [2][nb][k] block sums of the preconditioned vector
+    double* rho;              // [2][nb][4][k] block sums of phi times the preconditioned vector
     double* red;              // [2][nb][3k] block partial sums
     unsigned* bar;
     int* iters;
@@ -339,17 +471,18 @@ constexpr int kCrowMax = 7680;      // doubles of cached coarse-inverse rows (60
 template <int KG>
 struct PcgShared {
     float Binv[kBS * kBS];
-    double crow[kCrowMax];          // rows of C0inv of the neighbouring blocks
+    double crow[kCrowMax];          // rows of C0inv of the coarse functions of the touching aggregates
     double r[kBS * KG];
-    double rho[kMaxNbPcg * KG];
-    double c[kMaxNbn * KG];
-    double wave[(kThreads / 64) * 3 * KG];
-    double sums[3 * KG];
+    double rho[kCoarseMax * KG];    // coarse right-hand side [nc][KG] (and the block product's halves)
+    double c[kMaxAggNbn * 4 * KG];  // coarse values [slot][4][KG]
+    double wave[(kThreads / 64) * 4 * KG];
+    double sums[4 * KG];
     double coef[2 * KG];            // alpha, beta of every column
     int live[KG];                   // column not yet converged
     double part[kThreads];
-    int32_t nbl[kMaxNbn];
+    int32_t nbl[kMaxAggNbn];
 };
+static_assert(kCoarseMax >= kBS, "the block product's halves go through PcgShared::rho");
 
 // Sum of n values p[0], p[stride], ... in a fixed order: four interleaved partial sums, so
 // four loads are in flight at a time, added as (s0 + s1) + (s2 + s3).
@@ -419,7 +552,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         if ((int)blockIdx.x >= tab[q].block0) pm = q;
     const PcgArgs A = tab[pm];
     const int B = (int)blockIdx.x - A.block0;
-    const int nb = A.nb, k = A.k;
+    const int nb = A.nb, nc = A.nc, k = A.k;
     const int64_t n = A.n;
     const int32_t s0 = A.bstart[B], cnt = A.bstart[B + 1] - s0;
     // threads t < kBS own row s0 + t of the block (when t < cnt); threads kBS .. kThreads
@@ -433,41 +566,43 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         float4* dst = reinterpret_cast<float4*>(S.Binv);
         for (int q = t; q < kBS * kBS / 4; q += kThreads) dst[q] = src[q];
     }
-    const int nbo = A.badj_off[B], nbn = A.badj_off[B + 1] - nbo;
-    for (int q = t; q < nbn; q += kThreads) S.nbl[q] = A.badj[nbo + q];
+    // aggregates touching this block (slots), and the rows of C0inv of their coarse functions
+    const int nbo = A.abl_off[B], nsl = A.abl_off[B + 1] - nbo;
+    for (int q = t; q < nsl; q += kThreads) S.nbl[q] = A.abl[nbo + q];
     __syncthreads();
-    // rows of C0inv for the neighbouring blocks stay in LDS when they fit
-    const bool crow_lds = (int64_t)nbn * nb <= kCrowMax;
+    const bool crow_lds = (int64_t)nsl * 4 * nc <= kCrowMax;
     if (crow_lds)
-        for (int q = t; q < nbn * nb; q += kThreads) S.crow[q] = A.C0inv[(int64_t)S.nbl[q / nb] * nb + (q % nb)];
+        for (int q = t; q < nsl * 4 * nc; q += kThreads) {
+            const int row = q / nc;   // slot * 4 + function
+            S.crow[q] = A.C0inv[(int64_t)(4 * S.nbl[row / 4] + row % 4) * nc + (q % nc)];
+        }
     __syncthreads();
     int own_slot = 0;
-    for (int q = 0; q < nbn; ++q)
-        if (S.nbl[q] == B) own_slot = q;
+    {
+        const int own = A.agg_of_block[B];
+        for (int q = 0; q < nsl; ++q)
+            if (S.nbl[q] == own) own_slot = q;
+    }
 
     constexpr int kCache = 8;
     int32_t cj[kCache];
     double cv[kCache];
-    int cs[kCache];
 #pragma unroll
     for (int e = 0; e < kCache; ++e) {
         const bool in = act && e < A.ell_w;
         cj[e] = in ? A.pcol[(int64_t)e * n + i] : 0;
         cv[e] = in ? A.pval[(int64_t)e * n + i] : 0.0;
-        cs[e] = in ? A.pslot[(int64_t)e * n + i] : 0;
     }
-    // coarse part of a row of C M^{-1}: the row's entries added per neighbouring block (the
-    // first entry of each block carries the block's weight, the others weight 0)
-    double cw[kCache];
+    // the row's coarse functions and, per touched aggregate, the coarse part of its row of C
+    double phi[4], rwt[kPcgRowSlots][4];
+    int rsl[kPcgRowSlots];
 #pragma unroll
-    for (int e = 0; e < kCache; ++e) {
-        bool first = true;
+    for (int a = 0; a < 4; ++a) phi[a] = act ? A.phi[i * 4 + a] : 0.0;
 #pragma unroll
-        for (int f = 0; f < e; ++f) first = first && (cs[f] != cs[e] || f >= A.ell_w);
-        double w = 0.0;
+    for (int q = 0; q < kPcgRowSlots; ++q) {
+        rsl[q] = act ? (int)A.rslot[(int64_t)q * n + i] : -1;
 #pragma unroll
-        for (int f = e; f < kCache; ++f) w += (cs[f] == cs[e] && f < A.ell_w) ? cv[f] : 0.0;
-        cw[e] = (first && e < A.ell_w) ? w : 0.0;
+        for (int a = 0; a < 4; ++a) rwt[q][a] = (rsl[q] >= 0) ? A.rw[((int64_t)q * 4 + a) * n + i] : 0.0;
     }
 
     // Exchange buffers come in two copies: data published before the b-th barrier goes to
@@ -482,7 +617,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         return ok;
     };
     auto vbuf = [&](int c) { return A.Vb + (int64_t)c * n * k; };
-    auto rhob = [&](int c) { return A.rho + (int64_t)c * nb * k; };
+    auto rhob = [&](int c) { return A.rho + (int64_t)c * nb * 4 * k; };
     auto redb = [&](int c) { return A.red + (int64_t)c * nb * 3 * k; };
 
     // M sums over the nb blocks of the copy c of the published partials ([nb][3][k], the
@@ -554,15 +689,21 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
 #pragma unroll
             for (int c = 0; c < KG; ++c) v[c] += S.rho[t * KG + c];
         }
-        double tmp[KG];
+        // the block's share of the coarse right-hand side: sum over its rows of phi[a] y
+        double tmp[4 * KG];
 #pragma unroll
-        for (int c = 0; c < KG; ++c) tmp[c] = (act && c < k) ? y[c] : 0.0;
-        wg_reduce<KG>(tmp, S.wave, S.sums);
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < KG; ++c) tmp[a * KG + c] = (act && c < k) ? phi[a] * y[c] : 0.0;
+        wg_reduce<4 * KG>(tmp, S.wave, S.sums);
         if (act)
 #pragma unroll
             for (int c = 0; c < KG; ++c)
                 if (c < k) vbuf(cp)[i * k + c] = v[c];
-        if (t < KG && t < k) rhob(cp)[(int64_t)B * k + t] = S.sums[t];
+        if (t < 4 * KG) {
+            const int a = t / KG, c = t - a * KG;
+            if (c < k) rhob(cp)[((int64_t)B * 4 + a) * k + c] = S.sums[t];
+        }
         if (!sync()) return false;
         const double* Vb = vbuf(cp);
         const double* rho = rhob(cp);
@@ -576,32 +717,30 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
                 for (int c = 0; c < KG; ++c)
                     vnb[e][c] = (e < A.ell_w && c < k) ? Vb[(int64_t)cj[e] * k + c] : 0.0;
         }
-        // block sums of every block: four loads in flight per thread
-        for (int q0 = t; q0 < nb * KG; q0 += 4 * kThreads) {
-            double vv[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int qq = q0 + u * kThreads, bb = qq / KG, c = qq - bb * KG;
-                vv[u] = (qq < nb * KG && c < k) ? rho[(int64_t)bb * k + c] : 0.0;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (q0 + u * kThreads < nb * KG) S.rho[q0 + u * kThreads] = vv[u];
+        // coarse right-hand side [nc][KG]: function 4g + a sums the shares of aggregate g's
+        // blocks in block order
+        for (int q = t; q < nc * KG; q += kThreads) {
+            const int d = q / KG, c = q - d * KG, g = d / 4, a = d - 4 * g;
+            double acc = 0.0;
+            if (c < k)
+                for (int bb = A.astart[g]; bb < A.astart[g + 1]; ++bb) acc += rho[((int64_t)bb * 4 + a) * k + c];
+            S.rho[q] = acc;
         }
         __syncthreads();
-        // coarse values c(sl) = sum_bb C0inv[nbl[sl]][bb] rho[bb] for the nbn x KG jobs: each
-        // job's dot product is cut into P parts of consecutive blocks (one per thread)
-        const int jobs = nbn * KG;
+        // coarse values S.c[sl][a][c] = sum_d C0inv[4 nbl[sl] + a][d] rho[d][c] for the
+        // nsl x 4 x KG jobs: each job's dot product is cut into P parts (one per thread)
+        const int jobs = nsl * 4 * KG;
         for (int j0 = 0; j0 < jobs; j0 += kThreads) {
             const int nj = min(kThreads, jobs - j0);
             const int P = max(1, kThreads / nj);
-            const int chunk = (nb + P - 1) / P;
+            const int chunk = (nc + P - 1) / P;
             const int jl = t / P, part = t - jl * P;
             if (jl < nj) {
-                const int job = j0 + jl, sl = job / KG, c = job - sl * KG;
-                const double* row = crow_lds ? S.crow + sl * nb : A.C0inv + (int64_t)S.nbl[sl] * nb;
-                const int b0 = part * chunk, b1 = min(nb, b0 + chunk);
-                S.part[jl * P + part] = b1 > b0 ? dot_fixed(row + b0, S.rho + b0 * KG + c, b1 - b0, KG) : 0.0;
+                const int job = j0 + jl, row = job / KG, c = job - row * KG;   // row = slot * 4 + a
+                const double* crow = crow_lds ? S.crow + (int64_t)row * nc
+                                              : A.C0inv + (int64_t)(4 * S.nbl[row / 4] + row % 4) * nc;
+                const int d0 = part * chunk, d1 = min(nc, d0 + chunk);
+                S.part[jl * P + part] = d1 > d0 ? dot_fixed(crow + d0, S.rho + d0 * KG + c, d1 - d0, KG) : 0.0;
             }
             __syncthreads();
             if (t < nj) S.c[j0 + t] = sum_fixed(S.part + t * P, P, 1);
@@ -610,7 +749,10 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         double acc[KG];
 #pragma unroll
         for (int c = 0; c < KG; ++c) {
-            m[c] = v[c] + S.c[own_slot * KG + c];
+            double cm = 0.0;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) cm += phi[a] * S.c[(own_slot * 4 + a) * KG + c];
+            m[c] = v[c] + cm;
             acc[c] = 0.0;
         }
         if (act) {
@@ -619,18 +761,19 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
 #pragma unroll
                 for (int c = 0; c < KG; ++c) acc[c] += cv[e] * vnb[e][c];
 #pragma unroll
-            for (int e = 0; e < kCache; ++e)
-                if (cw[e] != 0.0) {
+            for (int q = 0; q < kPcgRowSlots; ++q)
+                if (rsl[q] >= 0) {
 #pragma unroll
-                    for (int c = 0; c < KG; ++c) acc[c] += cw[e] * S.c[cs[e] * KG + c];
+                    for (int a = 0; a < 4; ++a)
+#pragma unroll
+                        for (int c = 0; c < KG; ++c) acc[c] += rwt[q][a] * S.c[(rsl[q] * 4 + a) * KG + c];
                 }
-            for (int e = kCache; e < A.ell_w; ++e) {
+            for (int e = kCache; e < A.ell_w; ++e) {   // (their coarse part is in rwt)
                 const int32_t j = A.pcol[(int64_t)e * n + i];
                 const double a = A.pval[(int64_t)e * n + i];
-                const int sl = A.pslot[(int64_t)e * n + i];
 #pragma unroll
                 for (int c = 0; c < KG; ++c)
-                    if (c < k) acc[c] += a * (Vb[(int64_t)j * k + c] + S.c[sl * KG + c]);
+                    if (c < k) acc[c] += a * Vb[(int64_t)j * k + c];
             }
         }
 #pragma unroll
@@ -809,7 +952,7 @@ size_t pcg_smem_bytes(int kg)
     }
 }
 
-hipError_t launch_pcg_setup(const PcgSetup& ps, const int32_t* lap_off, const double* lap_val,
+hipError_t launch_pcg_setup(const PcgSetup& ps, const double* V, const int32_t* lap_off, const double* lap_val,
                             hipStream_t s)
 {
     hipLaunchKernelGGL(k_perm_ell_vals, dim3((unsigned)((ps.n + 255) / 256)), dim3(256), 0, s,
@@ -819,24 +962,31 @@ hipError_t launch_pcg_setup(const PcgSetup& ps, const int32_t* lap_off, const do
     const size_t binv_smem = sizeof(double) * kBS * kBS;
     e = hipFuncSetAttribute((const void*)k_block_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)binv_smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_block_inverse, dim3(ps.nb), dim3(256), binv_smem, s, ps.n, ps.ell_w, ps.pcol,
+    hipLaunchKernelGGL(k_block_inverse, dim3(ps.nb), dim3(kInvThreads), binv_smem, s, ps.n, ps.ell_w, ps.pcol,
                        ps.pval, ps.bstart, ps.whole, ps.Binv);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    double* bdiag = ps.C0inv + (int64_t)ps.nb * ps.nb;   // scratch tail of the C0inv buffer
-    hipLaunchKernelGGL(k_coarse_rows, dim3(ps.nb), dim3(64), sizeof(double) * ps.nb, s, ps.n, ps.ell_w,
-                       ps.nb, ps.pcol, ps.pval, ps.bstart, ps.blk, ps.C0inv, bdiag);
+    // coarse functions, their rows of C, the Galerkin matrix and its inverse
+    hipLaunchKernelGGL(k_agg_basis, dim3(ps.na), dim3(kAggThreads), 0, s, ps.perm, V, ps.astart, ps.bstart, ps.phi,
+                       ps.esum);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    if (ps.nb <= kCoarseSweepMax) {
-        const size_t sm = sizeof(double) * (size_t)ps.nb * (ps.nb + 1) / 2;
-        e = hipFuncSetAttribute((const void*)k_coarse_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(sizeof(double) * kCoarseSweepMax * (kCoarseSweepMax + 1) / 2));
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_coarse_sweep, dim3(1), dim3(kCoarseThreads), sm, s, ps.nb, ps.bcomp,
-                           ps.ncomp_blocks, bdiag, ps.C0inv);
-    } else {
-        hipLaunchKernelGGL(k_coarse_inverse, dim3(1), dim3(kCoarseThreads), 0, s, ps.nb, ps.bcomp,
-                           ps.ncomp_blocks, bdiag, ps.C0inv);
-    }
+    hipLaunchKernelGGL(k_row_coarse, dim3((unsigned)((ps.n + 255) / 256)), dim3(256), 0, s, ps.n, ps.ell_w, ps.pcol,
+                       ps.pval, ps.eslot, ps.phi, ps.rw);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t nn = (int64_t)ps.nc * ps.nc;
+    hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, s, ps.C0inv, nn);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t asm_smem = sizeof(double) * kAsmGroups * (size_t)ps.na * 16;
+    e = hipFuncSetAttribute((const void*)k_coarse_assemble, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(double) * kAsmGroups * (kCoarseMax / 4) * 16));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_coarse_assemble, dim3(ps.na), dim3(kAggThreads), asm_smem, s, ps.n, ps.na, ps.nc,
+                       ps.astart, ps.bstart, ps.blk, ps.abl_off, ps.abl, ps.rslot, ps.phi, ps.rw, ps.C0inv);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const size_t sm = sizeof(double) * (size_t)ps.nc * (ps.nc + 1) / 2;
+    e = hipFuncSetAttribute((const void*)k_coarse_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(sizeof(double) * kCoarseMax * (kCoarseMax + 1) / 2));
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_coarse_sweep, dim3(1), dim3(kCoarseThreads), sm, s, ps.nc, ps.acomp, ps.esum, ps.C0inv);
     return hipGetLastError();
 }
 
@@ -868,9 +1018,10 @@ const void* pcg_fn(int k)
 
 }  // namespace
 
-bool pcg_supported(int64_t nb, int ncomp_blocks_max) { (void)ncomp_blocks_max; return nb >= 1 && nb <= kMaxNbPcg; }
 int pcg_block_size() { return kBS; }
-int pcg_max_neighbors() { return kMaxNbn; }
+int pcg_max_blocks() { return kMaxNbPcg; }
+int pcg_max_coarse() { return kCoarseMax; }
+int pcg_max_block_aggregates() { return kMaxAggNbn; }
 size_t pcg_table_bytes(int n) { return sizeof(PcgArgs) * (size_t)std::max(n, 1); }
 
 hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, void* tab_host,
@@ -891,8 +1042,9 @@ hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, v
         const PcgItem& it = items[m];
         const PcgSetup& ps = *it.ps;
         PcgArgs& a = H[m];
-        a.n = ps.n; a.nb = ps.nb; a.ell_w = ps.ell_w; a.pcol = ps.pcol; a.pval = ps.pval; a.pslot = ps.pslot;
-        a.bstart = ps.bstart; a.badj_off = ps.badj_off; a.badj = ps.badj; a.Binv = ps.Binv; a.C0inv = ps.C0inv;
+        a.n = ps.n; a.nb = ps.nb; a.nc = ps.nc; a.ell_w = ps.ell_w; a.pcol = ps.pcol; a.pval = ps.pval;
+        a.bstart = ps.bstart; a.astart = ps.astart; a.agg_of_block = ps.agg_of_block; a.abl_off = ps.abl_off;
+        a.abl = ps.abl; a.rslot = ps.rslot; a.phi = ps.phi; a.rw = ps.rw; a.Binv = ps.Binv; a.C0inv = ps.C0inv;
         a.b = it.b; a.x = it.x; a.Vb = it.w.Vb; a.rho = it.w.rho; a.red = it.w.red; a.bar = it.w.bar;
         a.iters = it.w.iters; a.relres = it.w.relres; a.flags = it.w.flags;
         a.rtol = it.rtol; a.maxiter = it.maxiter; a.k = k; a.block0 = 0;
