@@ -388,26 +388,48 @@ __device__ __forceinline__ double wave_sum(double v)
     return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
+// Loads and stores of the data that workgroups of one launch exchange across a
+// group_barrier_direct: agent-scope relaxed atomics are made coherent at the device level
+// by the memory system itself (the store is written through the XCD's L2, the load misses
+// it), so no L2 write-back or invalidate is needed to pass them between XCDs.
+__device__ __forceinline__ void xstore(double* p, double v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double xload(const double* p)
+{
+    return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Barrier among the W workgroups of a group, the target-th of the launch (1, 2, ...): every
 // workgroup raises its own flag word (one 128-byte line each, zeroed before the launch) to
 // target, then all its threads poll the W flags (a few each) until all have reached it.
 // No atomic read-modify-write is involved, so arrivals do not serialise on a counter.
 // The workgroup barrier alone does not wait for global stores (it only orders them for
-// waves of the same CU), and a release by thread 0 waits for its own wave's stores only:
-// so every wave first waits until its own stores have been acknowledged by L2
-// (s_waitcnt vmcnt(0), immediate 0x0F70: expcnt and lgkmcnt at their maxima); thread 0's
-// agent-scope release store of the flag (L2 write-back first) then covers the stores of the
-// whole workgroup, and its acquire fence after the wait makes the other workgroups' stores
-// visible to the whole workgroup (the caches it invalidates are shared by the workgroup's
-// waves).  Spins are bounded: a wait that exceeds kSpinLimit, or sees the abort flag, sets
-// the abort flag and returns false in every workgroup.
-__device__ __forceinline__ bool group_barrier(unsigned* gbar, int w, int W, int* flags, unsigned target)
+// waves of the same CU): so every wave first waits until its own stores have been
+// acknowledged (s_waitcnt vmcnt(0), immediate 0x0F70: expcnt and lgkmcnt at their maxima),
+// and thread 0 raises the flag only after all waves have done so.
+//   FENCED: plain loads and stores may cross the barrier.  The flag store is an agent-scope
+//   release (the XCD's L2 is written back first) and an agent-scope acquire fence after
+//   the wait makes the other workgroups' stores visible to the whole workgroup (the caches
+//   it invalidates are shared by the workgroup's waves).
+//   Direct: only xstore / xload data may cross the barrier; their stores are complete at the
+//   device coherence point once acknowledged, so the flag is a relaxed store and no cache
+//   is written back or invalidated (about half the latency; the workgroup's L2 contents
+//   survive the barrier).
+// Spins are bounded: a wait that exceeds kSpinLimit, or sees the abort flag, sets the abort
+// flag and returns false in every workgroup.
+template <bool FENCED>
+__device__ __forceinline__ bool group_barrier_t(unsigned* gbar, int w, int W, int* flags, unsigned target)
 {
     __shared__ int ok_sh;
     __builtin_amdgcn_s_waitcnt(0x0F70);
     __syncthreads();
     if (threadIdx.x == 0) {
-        __hip_atomic_store(gbar + (size_t)w * kLine, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if (FENCED)
+            __hip_atomic_store(gbar + (size_t)w * kLine, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        else
+            __hip_atomic_store(gbar + (size_t)w * kLine, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         ok_sh = 1;
     }
     __syncthreads();
@@ -431,11 +453,20 @@ __device__ __forceinline__ bool group_barrier(unsigned* gbar, int w, int W, int*
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        if (FENCED) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         if (__hip_atomic_load(&flags[kFlagCgAbort], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok_sh = 0;
     }
     __syncthreads();
     return ok_sh != 0;
+}
+
+__device__ __forceinline__ bool group_barrier(unsigned* gbar, int w, int W, int* flags, unsigned target)
+{
+    return group_barrier_t<true>(gbar, w, W, flags, target);
+}
+__device__ __forceinline__ bool group_barrier_direct(unsigned* gbar, int w, int W, int* flags, unsigned target)
+{
+    return group_barrier_t<false>(gbar, w, W, flags, target);
 }
 
 #endif

@@ -502,6 +502,23 @@ __device__ __forceinline__ double sum_fixed(const double* __restrict__ p, int n,
     return (a0 + a1) + (a2 + a3);
 }
 
+// sum_fixed over values published by other workgroups (loaded with xload).
+__device__ __forceinline__ double sum_fixed_x(const double* __restrict__ p, int n, int64_t stride)
+{
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int i = 0;
+    for (; i + 4 <= n; i += 4) {
+        const double v0 = xload(p + (int64_t)i * stride), v1 = xload(p + (int64_t)(i + 1) * stride);
+        const double v2 = xload(p + (int64_t)(i + 2) * stride), v3 = xload(p + (int64_t)(i + 3) * stride);
+        a0 += v0;
+        a1 += v1;
+        a2 += v2;
+        a3 += v3;
+    }
+    for (; i < n; ++i) a0 += xload(p + (int64_t)i * stride);
+    return (a0 + a1) + (a2 + a3);
+}
+
 // Dot product sum_i a[i] b[i * bstride] in the same fixed order.
 __device__ __forceinline__ double dot_fixed(const double* __restrict__ a, const double* __restrict__ b, int n,
                                             int bstride)
@@ -612,7 +629,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
     auto pub = [&]() { return nbar & 1; };
     auto got = [&]() { return (nbar - 1) & 1; };
     auto sync = [&]() -> bool {
-        const bool ok = group_barrier(A.bar, B, nb, A.flags, (unsigned)nbar + 1u);
+        const bool ok = group_barrier_direct(A.bar, B, nb, A.flags, (unsigned)nbar + 1u);
         ++nbar;
         return ok;
     };
@@ -634,7 +651,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
             double acc = 0.0;
             if (cc < k) {
                 const int b0 = part * chunk, b1 = min(nb, b0 + chunk);
-                if (b1 > b0) acc = sum_fixed(red + (int64_t)b0 * 3 * k + g * k + cc, b1 - b0, 3 * k);
+                if (b1 > b0) acc = sum_fixed_x(red + (int64_t)b0 * 3 * k + g * k + cc, b1 - b0, 3 * k);
             }
             S.part[q * P + part] = acc;
         }
@@ -699,10 +716,10 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         if (act)
 #pragma unroll
             for (int c = 0; c < KG; ++c)
-                if (c < k) vbuf(cp)[i * k + c] = v[c];
+                if (c < k) xstore(vbuf(cp) + i * k + c, v[c]);
         if (t < 4 * KG) {
             const int a = t / KG, c = t - a * KG;
-            if (c < k) rhob(cp)[((int64_t)B * 4 + a) * k + c] = S.sums[t];
+            if (c < k) xstore(rhob(cp) + ((int64_t)B * 4 + a) * k + c, S.sums[t]);
         }
         if (!sync()) return false;
         const double* Vb = vbuf(cp);
@@ -715,7 +732,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
             for (int e = 0; e < kCache; ++e)
 #pragma unroll
                 for (int c = 0; c < KG; ++c)
-                    vnb[e][c] = (e < A.ell_w && c < k) ? Vb[(int64_t)cj[e] * k + c] : 0.0;
+                    vnb[e][c] = (e < A.ell_w && c < k) ? xload(Vb + (int64_t)cj[e] * k + c) : 0.0;
         }
         // coarse right-hand side [nc][KG]: function 4g + a sums the shares of aggregate g's
         // blocks in block order
@@ -723,7 +740,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
             const int d = q / KG, c = q - d * KG, g = d / 4, a = d - 4 * g;
             double acc = 0.0;
             if (c < k)
-                for (int bb = A.astart[g]; bb < A.astart[g + 1]; ++bb) acc += rho[((int64_t)bb * 4 + a) * k + c];
+                for (int bb = A.astart[g]; bb < A.astart[g + 1]; ++bb) acc += xload(rho + ((int64_t)bb * 4 + a) * k + c);
             S.rho[q] = acc;
         }
         __syncthreads();
@@ -773,7 +790,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
                 const double a = A.pval[(int64_t)e * n + i];
 #pragma unroll
                 for (int c = 0; c < KG; ++c)
-                    if (c < k) acc[c] += a * Vb[(int64_t)j * k + c];
+                    if (c < k) acc[c] += a * xload(Vb + (int64_t)j * k + c);
             }
         }
 #pragma unroll
@@ -796,7 +813,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         const int cp = pub();
         if (t < 3 * KG) {
             const int g = t / KG, c = t - g * KG;
-            if (c < k) redb(cp)[(int64_t)B * 3 * k + g * k + c] = S.sums[t];
+            if (c < k) xstore(redb(cp) + (int64_t)B * 3 * k + g * k + c, S.sums[t]);
         }
         if (!sync()) return false;
         grid_sum(std::integral_constant<int, 3 * KG>{}, cp);
@@ -808,7 +825,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         if (act)
 #pragma unroll
             for (int c = 0; c < KG; ++c)
-                if (c < k) A.x[i * k + c] = x[c];
+                if (c < k) xstore(A.x + i * k + c, x[c]);
         if (!sync()) return false;
         double acc[KG];
 #pragma unroll
@@ -819,13 +836,13 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
                 if (e < A.ell_w)
 #pragma unroll
                     for (int c = 0; c < KG; ++c)
-                        if (c < k) acc[c] += cv[e] * A.x[(int64_t)cj[e] * k + c];
+                        if (c < k) acc[c] += cv[e] * xload(A.x + (int64_t)cj[e] * k + c);
             for (int e = kCache; e < A.ell_w; ++e) {
                 const int32_t j = A.pcol[(int64_t)e * n + i];
                 const double a = A.pval[(int64_t)e * n + i];
 #pragma unroll
                 for (int c = 0; c < KG; ++c)
-                    if (c < k) acc[c] += a * A.x[(int64_t)j * k + c];
+                    if (c < k) acc[c] += a * xload(A.x + (int64_t)j * k + c);
             }
         }
         double tmp[KG];
@@ -836,7 +853,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         }
         wg_reduce<KG>(tmp, S.wave, S.sums);
         const int cp = pub();
-        if (t < KG && t < k) redb(cp)[(int64_t)B * 3 * k + t] = S.sums[t];
+        if (t < KG && t < k) xstore(redb(cp) + (int64_t)B * 3 * k + t, S.sums[t]);
         if (!sync()) return false;
         grid_sum(std::integral_constant<int, KG>{}, cp);
         return true;
