@@ -41,6 +41,7 @@ constexpr int kThreads = 2 * kBS;   // threads per solver workgroup: row owners 
 constexpr int kMaxAggNbn = 16;      // aggregates touching a block (its own included)
 constexpr int kMaxNbPcg = 256;      // blocks (one co-resident workgroup per block)
 static_assert(kMaxNbPcg <= kMaxBarrierW, "one barrier flag per block");
+constexpr int kMaxAggBlocks = 6;    // blocks per aggregate: ceil(4 kMaxNbPcg / kCoarseMax)
 
 // ---------------------------------------------------------------- per-geometry setup
 
@@ -342,6 +343,7 @@ __global__ __launch_bounds__(kAggThreads) void k_coarse_assemble(int64_t n, int 
 constexpr int kCoarseThreads = 1024;
 constexpr int kCoarseMax = 200;   // packed upper triangle: 200 x 201 / 2 doubles = 157 KB of LDS
 constexpr int kMaxCoarseComp = kCoarseMax / 4;
+static_assert(kMaxAggBlocks * kCoarseMax >= 4 * kMaxNbPcg, "aggregates of up to kMaxAggBlocks blocks");
 
 // nc <= kCoarseMax: symmetric sweeps in LDS on the packed upper triangle (row i holds
 // columns i .. nc-1).  Sweeping pivot k with d = a_kk maps a_ij -> a_ij - a_ik a_kj / d
@@ -481,6 +483,7 @@ struct PcgShared {
     int live[KG];                   // column not yet converged
     double part[kThreads];
     int32_t nbl[kMaxAggNbn];
+    int32_t ast[kCoarseMax / 4 + 1];  // first block of each aggregate
 };
 static_assert(kCoarseMax >= kBS, "the block product's halves go through PcgShared::rho");
 
@@ -502,21 +505,20 @@ __device__ __forceinline__ double sum_fixed(const double* __restrict__ p, int n,
     return (a0 + a1) + (a2 + a3);
 }
 
-// sum_fixed over values published by other workgroups (loaded with xload).
+// Sum in a fixed order of n values published by other workgroups (loaded with xload):
+// the loads of 8 values at a time are all in flight before they are added, value i to
+// partial sum i % 4, and the partial sums are added as (s0 + s1) + (s2 + s3).
 __device__ __forceinline__ double sum_fixed_x(const double* __restrict__ p, int n, int64_t stride)
 {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int i = 0;
-    for (; i + 4 <= n; i += 4) {
-        const double v0 = xload(p + (int64_t)i * stride), v1 = xload(p + (int64_t)(i + 1) * stride);
-        const double v2 = xload(p + (int64_t)(i + 2) * stride), v3 = xload(p + (int64_t)(i + 3) * stride);
-        a0 += v0;
-        a1 += v1;
-        a2 += v2;
-        a3 += v3;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < n; i += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = i + u < n ? xload(p + (int64_t)(i + u) * stride) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u & 3] += v[u];
     }
-    for (; i < n; ++i) a0 += xload(p + (int64_t)i * stride);
-    return (a0 + a1) + (a2 + a3);
+    return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
 // Dot product sum_i a[i] b[i * bstride] in the same fixed order.
@@ -586,6 +588,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
     // aggregates touching this block (slots), and the rows of C0inv of their coarse functions
     const int nbo = A.abl_off[B], nsl = A.abl_off[B + 1] - nbo;
     for (int q = t; q < nsl; q += kThreads) S.nbl[q] = A.abl[nbo + q];
+    for (int q = t; q <= nc / 4; q += kThreads) S.ast[q] = A.astart[q];
     __syncthreads();
     const bool crow_lds = (int64_t)nsl * 4 * nc <= kCrowMax;
     if (crow_lds)
@@ -735,13 +738,39 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
                     vnb[e][c] = (e < A.ell_w && c < k) ? xload(Vb + (int64_t)cj[e] * k + c) : 0.0;
         }
         // coarse right-hand side [nc][KG]: function 4g + a sums the shares of aggregate g's
-        // blocks in block order
-        for (int q = t; q < nc * KG; q += kThreads) {
-            const int d = q / KG, c = q - d * KG, g = d / 4, a = d - 4 * g;
-            double acc = 0.0;
-            if (c < k)
-                for (int bb = A.astart[g]; bb < A.astart[g + 1]; ++bb) acc += xload(rho + ((int64_t)bb * 4 + a) * k + c);
-            S.rho[q] = acc;
+        // blocks in block order.  Jobs q = t + jj kThreads of this thread: the loads of kJB
+        // jobs (all of them for up to 3 columns; 2 at a time for more, to bound the registers
+        // held) are issued before any is added.  An aggregate holds at most kMaxAggBlocks
+        // blocks (the host never forms larger ones; any further blocks are added afterwards).
+        constexpr int kJ = (kCoarseMax * KG + kThreads - 1) / kThreads;
+        constexpr int kJB = KG <= 3 ? kJ : 2;
+#pragma unroll 1
+        for (int j0 = 0; j0 < kJ; j0 += kJB) {
+            double sh[kJB][kMaxAggBlocks];
+#pragma unroll
+            for (int jj = 0; jj < kJB; ++jj) {
+                const int q = t + (j0 + jj) * kThreads;
+                const int d = q / KG, c = q - d * KG, g = d / 4, a = d - 4 * g;
+                const bool on = q < nc * KG && c < k;
+                const int b0 = on ? S.ast[g] : 0, cntb = on ? S.ast[g + 1] - b0 : 0;
+#pragma unroll
+                for (int u = 0; u < kMaxAggBlocks; ++u)
+                    sh[jj][u] = u < cntb ? xload(rho + ((int64_t)(b0 + u) * 4 + a) * k + c) : 0.0;
+            }
+#pragma unroll
+            for (int jj = 0; jj < kJB; ++jj) {
+                const int q = t + (j0 + jj) * kThreads;
+                if (q < nc * KG) {
+                    const int d = q / KG, c = q - d * KG, g = d / 4, a = d - 4 * g;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int u = 0; u < kMaxAggBlocks; ++u) acc += sh[jj][u];
+                    if (c < k)
+                        for (int bb = S.ast[g] + kMaxAggBlocks; bb < S.ast[g + 1]; ++bb)
+                            acc += xload(rho + ((int64_t)bb * 4 + a) * k + c);
+                    S.rho[q] = acc;
+                }
+            }
         }
         __syncthreads();
         // coarse values S.c[sl][a][c] = sum_d C0inv[4 nbl[sl] + a][d] rho[d][c] for the
