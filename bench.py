@@ -340,6 +340,10 @@ def main():
     x = torch.empty_like(dE)
 
     def step():
+        # a descent step sees new vertex positions: the face data, the cotan Laplacian's
+        # values, the preconditioner's block and coarse inverses and the near-field grid
+        # are all formed again from them
+        P.set_vertices(V)
         E, _ = P.gradient(out=dE)
         P.fractional_apply(u, out=Lu)
         _, rep = P.precond_apply(dE, out=x)
@@ -407,8 +411,10 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": ("torus40k: torus R=1 r=0.3 on a 200x100 grid (40,000 faces), vertex noise "
-                         "0.002 r seed 0; per step E+dE, L^sigma u (u~N(0,1), k=3), and "
-                         "C^-1 L^sigma C^-1 dE with two FP64 CG solves to 1e-10"),
+                         "0.002 r seed 0; per step: vertex positions set (face data, cotan "
+                         "Laplacian values, preconditioner set-up and near-field grid formed "
+                         "again), E+dE, L^sigma u (u~N(0,1), k=3), and C^-1 L^sigma C^-1 dE with "
+                         "two FP64 CG solves to 1e-10"),
             "faces": nF,
             "vertices": mesh.nV,
             "alpha": 6, "beta": 12, "sigma": 1.0 / 3.0,

@@ -41,7 +41,7 @@ constexpr int kThreads = 2 * kBS;   // threads per solver workgroup: row owners 
 constexpr int kMaxAggNbn = 16;      // aggregates touching a block (its own included)
 constexpr int kMaxNbPcg = 256;      // blocks (one co-resident workgroup per block)
 static_assert(kMaxNbPcg <= kMaxBarrierW, "one barrier flag per block");
-constexpr int kMaxAggBlocks = 6;    // blocks per aggregate: ceil(4 kMaxNbPcg / kCoarseMax)
+constexpr int kMaxAggBlocks = 7;    // blocks per aggregate: ceil(4 kMaxNbPcg / kCoarseMax)
 
 // ---------------------------------------------------------------- per-geometry setup
 
@@ -60,7 +60,55 @@ __global__ void k_perm_ell_vals(int64_t n, int w, const int32_t* __restrict__ pe
 
 // Dense inverse of each diagonal block (Gauss-Jordan in LDS; the block is symmetric
 // positive definite, or made so by the rank-one term, so no pivoting is needed).
-constexpr int kInvThreads = 256;
+// In-place Gauss-Jordan inverse of an n x n symmetric positive definite matrix (no
+// pivoting) held in registers: the matrix is NC x NC (NC = TPR * CPT, rows and columns
+// n .. NC-1 zero), thread (row, part) holding a[c] = A[row][part * CPT + c].  Pivot k with
+// d = a_kk and g_i = a_ik / d:
+//   a_ij -> a_ij - g_i a_kj (i, j != k),  a_kj -> a_kj / d,  a_ik -> -g_i,  a_kk -> 1 / d;
+// row k takes the same multiply-add as the others with the multiplier 1 - 1/d.  Per pivot
+// the pivot row and column pass through LDS (two copies, alternating, so one workgroup
+// barrier per pivot suffices: a copy is written again only two pivots later, after every
+// thread has passed the barrier in between).  The pivot index within a thread's columns
+// is a compile-time constant of the unrolled inner loop, so the row stays in registers.
+// on: the thread holds a row (threads beyond NC * TPR only join the barriers).
+template <int TPR, int CPT>
+__device__ __forceinline__ void gj_inverse_regs(double (&a)[CPT], bool on, int row, int part, int n,
+                                                double* prow, double* fcol)
+{
+    constexpr int NC = TPR * CPT;
+    int buf = 0;
+    for (int kp = 0; kp < TPR && kp * CPT < n; ++kp) {
+#pragma unroll
+        for (int kk = 0; kk < CPT; ++kk) {
+            const int k = kp * CPT + kk;
+            if (k < n) {
+                double* pr = prow + buf * NC;
+                double* fc = fcol + buf * NC;
+                if (on && row == k) {
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) pr[part * CPT + c] = a[c];
+                }
+                if (on && part == kp) fc[row] = a[kk];
+                __syncthreads();
+                const double invd = 1.0 / pr[k];
+                const double g = on ? fc[row] * invd : 0.0;
+                const double h = row == k ? 1.0 - invd : g;
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    a[c] = __builtin_fma(-h, pr[part * CPT + c], a[c]);
+                    // at most 16 pivot-row values in registers at a time
+                    if ((c & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+                }
+                if (part == kp) a[kk] = row == k ? invd : -g;
+                buf ^= 1;
+            }
+        }
+    }
+}
+
+// Block inverses: one workgroup per block; kInvThreads = kBS rows x 4 parts of 32 columns.
+constexpr int kInvThreads = 512;
+constexpr int kInvParts = kInvThreads / kBS;
 __global__ __launch_bounds__(kInvThreads) void k_block_inverse(int64_t n, int w, const int32_t* __restrict__ pcol,
                                                        const double* __restrict__ pval,
                                                        const int32_t* __restrict__ bstart,
@@ -68,7 +116,7 @@ __global__ __launch_bounds__(kInvThreads) void k_block_inverse(int64_t n, int w,
                                                        float* __restrict__ Binv)
 {
     extern __shared__ __align__(16) double A[];   // kBS x kBS, row-major
-    __shared__ double fcol[kBS];
+    __shared__ double prow[2 * kBS], fcol[2 * kBS];
     const int B = blockIdx.x;
     const int32_t s0 = bstart[B], cnt = bstart[B + 1] - s0;
     for (int t = threadIdx.x; t < kBS * kBS; t += kInvThreads) A[t] = 0.0;
@@ -98,26 +146,16 @@ __global__ __launch_bounds__(kInvThreads) void k_block_inverse(int64_t n, int w,
         for (int t = threadIdx.x; t < cnt * cnt; t += kInvThreads) A[(t / cnt) * kBS + (t % cnt)] += add;
         __syncthreads();
     }
-    for (int k = 0; k < kBS; ++k) {
-        const double p = 1.0 / A[k * kBS + k];
-        __syncthreads();
-        if (threadIdx.x < kBS) fcol[threadIdx.x] = A[threadIdx.x * kBS + k];   // column k before the update
-        __syncthreads();
-        if (threadIdx.x < kBS) A[k * kBS + threadIdx.x] = (threadIdx.x == k ? 1.0 : A[k * kBS + threadIdx.x]) * p;
-        __syncthreads();
-        // each thread updates kBS * kBS / kInvThreads entries of one column, all loads issued
-        // together
-        const int j = threadIdx.x & (kBS - 1);
-        const double akj = A[k * kBS + j];
-#pragma unroll 16
-        for (int i = threadIdx.x / kBS; i < kBS; i += kInvThreads / kBS) {
-            if (i != k) {
-                const double base = (j == k) ? 0.0 : A[i * kBS + j];
-                A[i * kBS + j] = base - fcol[i] * akj;
-            }
-        }
-        __syncthreads();
-    }
+    constexpr int CPT = kBS / kInvParts;
+    const int row = threadIdx.x / kInvParts, part = threadIdx.x % kInvParts;
+    double a[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) a[c] = A[row * kBS + part * CPT + c];
+    gj_inverse_regs<kInvParts, CPT>(a, true, row, part, kBS, prow, fcol);
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) A[row * kBS + part * CPT + c] = a[c];
+    __syncthreads();
     // symmetrize (the elimination leaves rounding-level asymmetry) and round to FP32
     float* dst = Binv + (int64_t)B * kBS * kBS;
     for (int t = threadIdx.x; t < kBS * kBS; t += kInvThreads) {
@@ -340,79 +378,76 @@ __global__ __launch_bounds__(kAggThreads) void k_coarse_assemble(int64_t n, int 
 // dmean the mean of the kept diagonal entries; the action on per-component mean-zero vectors
 // is that of the pseudo-inverse.  The matrix is symmetric positive definite, so no pivoting
 // is needed.
-constexpr int kCoarseThreads = 1024;
-constexpr int kCoarseMax = 200;   // packed upper triangle: 200 x 201 / 2 doubles = 157 KB of LDS
+constexpr int kCoarseThreads = 640;
+constexpr int kCoarseMax = 160;
+constexpr int kCoarseParts = 4;                       // threads per row
+constexpr int kCoarseCols = kCoarseMax / kCoarseParts;  // columns per thread
+static_assert(kCoarseMax * kCoarseParts <= kCoarseThreads, "one thread per row part");
 constexpr int kMaxCoarseComp = kCoarseMax / 4;
 static_assert(kMaxAggBlocks * kCoarseMax >= 4 * kMaxNbPcg, "aggregates of up to kMaxAggBlocks blocks");
 
-// nc <= kCoarseMax: symmetric sweeps in LDS on the packed upper triangle (row i holds
-// columns i .. nc-1).  Sweeping pivot k with d = a_kk maps a_ij -> a_ij - a_ik a_kj / d
-// (i, j != k), a_ik -> a_ik / d, a_kk -> -1 / d; after all pivots the matrix is -A^{-1}.
-// Rows are spread over the waves, columns over the lanes.
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse_sweep(int nc, const int32_t* __restrict__ acomp,
+// One workgroup: the regularised matrix is formed in registers (kCoarseParts threads per
+// row), inverted there (gj_inverse_regs) and written over G, each entry pair (i, j), (j, i)
+// from the upper triangle, so the result is exactly symmetric.
+__global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(int nc, const int32_t* __restrict__ acomp,
                                                                  const double* __restrict__ esum,
                                                                  double* __restrict__ G)
 {
-    extern __shared__ __align__(16) double A[];
-    __shared__ double fcol[kCoarseMax];
+    __shared__ double prow[2 * kCoarseMax], fcol[2 * kCoarseMax];
+    __shared__ double diag[kCoarseMax], es[kCoarseMax];
+    __shared__ int32_t comp[kCoarseMax];
+    __shared__ double enorm[kMaxCoarseComp];   // e^T e per component
     __shared__ double dmean_sh;
-    __shared__ double enorm[kMaxCoarseComp];   // e^T e per component, indexed by first aggregate's slot
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    constexpr int kWaves = kCoarseThreads / 64;
-    auto off = [&](int i) { return i * nc - (i * (i - 1)) / 2; };
-    if (threadIdx.x == 0) {
+    const int t = threadIdx.x;
+    if (t < nc) {
+        diag[t] = G[(int64_t)t * nc + t];
+        es[t] = esum[t];
+        comp[t] = acomp[t / 4];   // components are numbered densely over the aggregates
+    }
+    __syncthreads();
+    if (t == 0) {
         double sd = 0.0;
         int cnt = 0;
         for (int i = 0; i < nc; ++i)
-            if (G[(int64_t)i * nc + i] > 0.0) {
-                sd += G[(int64_t)i * nc + i];
+            if (diag[i] > 0.0) {
+                sd += diag[i];
                 ++cnt;
             }
         dmean_sh = cnt > 0 ? sd / cnt : 1.0;
-        for (int q = 0; q < kMaxCoarseComp; ++q) enorm[q] = 0.0;
-        // components are numbered densely over the aggregates (acomp < nc / 4)
-        for (int i = 0; i < nc; ++i) enorm[acomp[i / 4]] += esum[i] * esum[i];
+    }
+    if (t < kMaxCoarseComp) {
+        double en = 0.0;
+        for (int i = 0; i < nc; ++i)
+            if (comp[i] == t) en += es[i] * es[i];
+        enorm[t] = en;
     }
     __syncthreads();
     const double dmean = dmean_sh;
-    for (int i = wave; i < nc; i += kWaves)
-        for (int j = i + lane; j < nc; j += 64) {
+    const int row = t / kCoarseParts, part = t % kCoarseParts;
+    const bool on = row < nc;
+    double a[kCoarseCols];
+#pragma unroll
+    for (int c = 0; c < kCoarseCols; ++c) {
+        const int j = part * kCoarseCols + c;
+        double v = 0.0;
+        if (on && j < nc) {
             // the two triangles are assembled by different aggregates: their mean is used
-            double v = 0.5 * (G[(int64_t)i * nc + j] + G[(int64_t)j * nc + i]);
-            const int ci = acomp[i / 4];
-            if (ci == acomp[j / 4] && enorm[ci] > 0.0) v += dmean * esum[i] * esum[j] / enorm[ci];
-            if (i == j && !(G[(int64_t)i * nc + i] > 0.0)) v = 1.0;   // dropped coarse function
-            A[off(i) + j - i] = v;
+            v = 0.5 * (G[(int64_t)row * nc + j] + G[(int64_t)j * nc + row]);
+            const int ci = comp[row];
+            if (ci == comp[j] && enorm[ci] > 0.0) v += dmean * es[row] * es[j] / enorm[ci];
+            if (row == j && !(diag[row] > 0.0)) v = 1.0;   // dropped coarse function
         }
-    __syncthreads();
-    for (int k = 0; k < nc; ++k) {
-        const double d = A[off(k)];
-        if ((int)threadIdx.x < nc) {
-            const int i = threadIdx.x;
-            fcol[i] = i <= k ? A[off(i) + k - i] : A[off(k) + i - k];
-        }
-        __syncthreads();
-        const double invd = 1.0 / d;
-        for (int i = wave; i < nc; i += kWaves) {
-            const double fi = fcol[i];
-            for (int j = i + lane; j < nc; j += 64) {
-                const int idx = off(i) + j - i;
-                double v;
-                if (i == k && j == k) v = -invd;
-                else if (i == k) v = fcol[j] * invd;
-                else if (j == k) v = fi * invd;
-                else v = A[idx] - fi * fcol[j] * invd;
-                A[idx] = v;
-            }
-        }
-        __syncthreads();
+        a[c] = v;
     }
-    for (int i = wave; i < nc; i += kWaves)
-        for (int j = i + lane; j < nc; j += 64) {
-            const double v = -A[off(i) + j - i];
-            G[(int64_t)i * nc + j] = v;
-            G[(int64_t)j * nc + i] = v;
+    gj_inverse_regs<kCoarseParts, kCoarseCols>(a, on, row, part, nc, prow, fcol);
+#pragma unroll
+    for (int c = 0; c < kCoarseCols; ++c) {
+        const int j = part * kCoarseCols + c;
+        if (on && j < nc && j >= row) {
+            G[(int64_t)row * nc + j] = a[c];
+            G[(int64_t)j * nc + row] = a[c];
         }
+    }
 }
 
 __global__ void k_fill_zero(double* __restrict__ p, int64_t n)
@@ -1028,11 +1063,7 @@ hipError_t launch_pcg_setup(const PcgSetup& ps, const double* V, const int32_t* 
     hipLaunchKernelGGL(k_coarse_assemble, dim3(ps.na), dim3(kAggThreads), asm_smem, s, ps.n, ps.na, ps.nc,
                        ps.astart, ps.bstart, ps.blk, ps.abl_off, ps.abl, ps.rslot, ps.phi, ps.rw, ps.C0inv);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const size_t sm = sizeof(double) * (size_t)ps.nc * (ps.nc + 1) / 2;
-    e = hipFuncSetAttribute((const void*)k_coarse_sweep, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(sizeof(double) * kCoarseMax * (kCoarseMax + 1) / 2));
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_coarse_sweep, dim3(1), dim3(kCoarseThreads), sm, s, ps.nc, ps.acomp, ps.esum, ps.C0inv);
+    hipLaunchKernelGGL(k_coarse_inverse, dim3(1), dim3(kCoarseThreads), 0, s, ps.nc, ps.acomp, ps.esum, ps.C0inv);
     return hipGetLastError();
 }
 
