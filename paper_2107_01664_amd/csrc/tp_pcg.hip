@@ -61,54 +61,73 @@ __global__ void k_perm_ell_vals(int64_t n, int w, const int32_t* __restrict__ pe
 // Dense inverse of each diagonal block (Gauss-Jordan in LDS; the block is symmetric
 // positive definite, or made so by the rank-one term, so no pivoting is needed).
 // In-place Gauss-Jordan inverse of an n x n symmetric positive definite matrix (no
-// pivoting) held in registers: the matrix is NC x NC (NC = TPR * CPT, rows and columns
-// n .. NC-1 zero), thread (row, part) holding a[c] = A[row][part * CPT + c].  Pivot k with
-// d = a_kk and g_i = a_ik / d:
+// pivoting) held in registers.  The matrix is NC x NC (NC = RB * NRB = CB * NCB; rows and
+// columns n .. NC-1 zero); thread t < NRB * NCB holds the RB x CB tile a[r][c] =
+// A[rb RB + r][cb CB + c] with rb = t % NRB, cb = t / NRB.  Pivot k with d = a_kk and
+// g_i = a_ik / d:
 //   a_ij -> a_ij - g_i a_kj (i, j != k),  a_kj -> a_kj / d,  a_ik -> -g_i,  a_kk -> 1 / d;
 // row k takes the same multiply-add as the others with the multiplier 1 - 1/d.  Per pivot
 // the pivot row and column pass through LDS (two copies, alternating, so one workgroup
 // barrier per pivot suffices: a copy is written again only two pivots later, after every
-// thread has passed the barrier in between).  The pivot index within a thread's columns
-// is a compile-time constant of the unrolled inner loop, so the row stays in registers.
-// on: the thread holds a row (threads beyond NC * TPR only join the barriers).
-template <int TPR, int CPT>
-__device__ __forceinline__ void gj_inverse_regs(double (&a)[CPT], bool on, int row, int part, int n,
-                                                double* prow, double* fcol)
+// thread has passed the barrier in between); a thread reads CB + RB of their values for
+// its RB CB multiply-adds.  The pivot's position within a tile is a compile-time constant
+// of the unrolled inner loop (its length L is a multiple of RB and CB), so the tile stays
+// in registers.  Threads t >= NRB * NCB only join the barriers.
+template <int RB, int CB, int NRB, int NCB>
+__device__ __forceinline__ void gj_inverse_tiles(double (&a)[RB][CB], int n, double* prow, double* fcol)
 {
-    constexpr int NC = TPR * CPT;
+    constexpr int NC = RB * NRB;
+    static_assert(CB * NCB == NC, "square tiling");
+    constexpr int L = RB * CB / (RB % CB == 0 ? CB : (CB % RB == 0 ? RB : 1));   // RB, CB | L
+    static_assert(L % RB == 0 && L % CB == 0, "unrolled pivots cover whole tiles");
+    const int t = threadIdx.x;
+    const bool on = t < NRB * NCB;
+    const int rb = t % NRB, cb = t / NRB;
     int buf = 0;
-    for (int kp = 0; kp < TPR && kp * CPT < n; ++kp) {
+    for (int k0 = 0; k0 < n; k0 += L) {
 #pragma unroll
-        for (int kk = 0; kk < CPT; ++kk) {
-            const int k = kp * CPT + kk;
+        for (int kk = 0; kk < L; ++kk) {
+            const int k = k0 + kk;
             if (k < n) {
+                const int rk = kk % RB, ck = kk % CB;   // position of row / column k in a tile
                 double* pr = prow + buf * NC;
                 double* fc = fcol + buf * NC;
-                if (on && row == k) {
+                if (on && rb == k / RB) {
 #pragma unroll
-                    for (int c = 0; c < CPT; ++c) pr[part * CPT + c] = a[c];
+                    for (int c = 0; c < CB; ++c) pr[cb * CB + c] = a[rk][c];
                 }
-                if (on && part == kp) fc[row] = a[kk];
+                if (on && cb == k / CB) {
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) fc[rb * RB + r] = a[r][ck];
+                }
                 __syncthreads();
                 const double invd = 1.0 / pr[k];
-                const double g = on ? fc[row] * invd : 0.0;
-                const double h = row == k ? 1.0 - invd : g;
+                if (on) {
+                    double p[CB], g[RB], h[RB];
 #pragma unroll
-                for (int c = 0; c < CPT; ++c) {
-                    a[c] = __builtin_fma(-h, pr[part * CPT + c], a[c]);
-                    // at most 16 pivot-row values in registers at a time
-                    if ((c & 15) == 15) __builtin_amdgcn_sched_barrier(0);
+                    for (int c = 0; c < CB; ++c) p[c] = pr[cb * CB + c];
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) {
+                        g[r] = fc[rb * RB + r] * invd;
+                        h[r] = rb * RB + r == k ? 1.0 - invd : g[r];
+                    }
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+#pragma unroll
+                        for (int c = 0; c < CB; ++c) a[r][c] = __builtin_fma(-h[r], p[c], a[r][c]);
+                    if (cb == k / CB) {
+#pragma unroll
+                        for (int r = 0; r < RB; ++r) a[r][ck] = rb * RB + r == k ? invd : -g[r];
+                    }
                 }
-                if (part == kp) a[kk] = row == k ? invd : -g;
                 buf ^= 1;
             }
         }
     }
 }
 
-// Block inverses: one workgroup per block; kInvThreads = kBS rows x 4 parts of 32 columns.
+// Block inverses: one workgroup per block.
 constexpr int kInvThreads = 512;
-constexpr int kInvParts = kInvThreads / kBS;
 __global__ __launch_bounds__(kInvThreads) void k_block_inverse(int64_t n, int w, const int32_t* __restrict__ pcol,
                                                        const double* __restrict__ pval,
                                                        const int32_t* __restrict__ bstart,
@@ -146,15 +165,21 @@ __global__ __launch_bounds__(kInvThreads) void k_block_inverse(int64_t n, int w,
         for (int t = threadIdx.x; t < cnt * cnt; t += kInvThreads) A[(t / cnt) * kBS + (t % cnt)] += add;
         __syncthreads();
     }
-    constexpr int CPT = kBS / kInvParts;
-    const int row = threadIdx.x / kInvParts, part = threadIdx.x % kInvParts;
-    double a[CPT];
+    // tiles of 4 rows x 8 columns: 32 row blocks x 16 column blocks
+    constexpr int RB = 4, CB = 8, NRB = kBS / RB, NCB = kBS / CB;
+    static_assert(NRB * NCB == kInvThreads, "one tile per thread");
+    const int rb = threadIdx.x % NRB, cb = threadIdx.x / NRB;
+    double a[RB][CB];
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) a[c] = A[row * kBS + part * CPT + c];
-    gj_inverse_regs<kInvParts, CPT>(a, true, row, part, kBS, prow, fcol);
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) a[r][c] = A[(rb * RB + r) * kBS + cb * CB + c];
+    gj_inverse_tiles<RB, CB, NRB, NCB>(a, kBS, prow, fcol);
     __syncthreads();
 #pragma unroll
-    for (int c = 0; c < CPT; ++c) A[row * kBS + part * CPT + c] = a[c];
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) A[(rb * RB + r) * kBS + cb * CB + c] = a[r][c];
     __syncthreads();
     // symmetrize (the elimination leaves rounding-level asymmetry) and round to FP32
     float* dst = Binv + (int64_t)B * kBS * kBS;
@@ -378,16 +403,17 @@ __global__ __launch_bounds__(kAggThreads) void k_coarse_assemble(int64_t n, int 
 // dmean the mean of the kept diagonal entries; the action on per-component mean-zero vectors
 // is that of the pseudo-inverse.  The matrix is symmetric positive definite, so no pivoting
 // is needed.
-constexpr int kCoarseThreads = 640;
+constexpr int kCoarseThreads = 512;
 constexpr int kCoarseMax = 160;
-constexpr int kCoarseParts = 4;                       // threads per row
-constexpr int kCoarseCols = kCoarseMax / kCoarseParts;  // columns per thread
-static_assert(kCoarseMax * kCoarseParts <= kCoarseThreads, "one thread per row part");
+// tiles of 5 rows x 10 columns: 32 row blocks x 16 column blocks
+constexpr int kCoarseRB = 5, kCoarseCB = 10;
+constexpr int kCoarseNRB = kCoarseMax / kCoarseRB, kCoarseNCB = kCoarseMax / kCoarseCB;
+static_assert(kCoarseNRB * kCoarseNCB <= kCoarseThreads, "one tile per thread");
 constexpr int kMaxCoarseComp = kCoarseMax / 4;
 static_assert(kMaxAggBlocks * kCoarseMax >= 4 * kMaxNbPcg, "aggregates of up to kMaxAggBlocks blocks");
 
-// One workgroup: the regularised matrix is formed in registers (kCoarseParts threads per
-// row), inverted there (gj_inverse_regs) and written over G, each entry pair (i, j), (j, i)
+// One workgroup: the regularised matrix is formed in registers (a tile per thread),
+// inverted there (gj_inverse_tiles) and written over G, each entry pair (i, j), (j, i)
 // from the upper triangle, so the result is exactly symmetric.
 __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(int nc, const int32_t* __restrict__ acomp,
                                                                  const double* __restrict__ esum,
@@ -423,31 +449,38 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(int nc, const
     }
     __syncthreads();
     const double dmean = dmean_sh;
-    const int row = t / kCoarseParts, part = t % kCoarseParts;
-    const bool on = row < nc;
-    double a[kCoarseCols];
+    constexpr int RB = kCoarseRB, CB = kCoarseCB, NRB = kCoarseNRB, NCB = kCoarseNCB;
+    const bool on = t < NRB * NCB;
+    const int rb = t % NRB, cb = t / NRB;
+    double a[RB][CB];
 #pragma unroll
-    for (int c = 0; c < kCoarseCols; ++c) {
-        const int j = part * kCoarseCols + c;
-        double v = 0.0;
-        if (on && j < nc) {
-            // the two triangles are assembled by different aggregates: their mean is used
-            v = 0.5 * (G[(int64_t)row * nc + j] + G[(int64_t)j * nc + row]);
-            const int ci = comp[row];
-            if (ci == comp[j] && enorm[ci] > 0.0) v += dmean * es[row] * es[j] / enorm[ci];
-            if (row == j && !(diag[row] > 0.0)) v = 1.0;   // dropped coarse function
-        }
-        a[c] = v;
-    }
-    gj_inverse_regs<kCoarseParts, kCoarseCols>(a, on, row, part, nc, prow, fcol);
+    for (int r = 0; r < RB; ++r)
 #pragma unroll
-    for (int c = 0; c < kCoarseCols; ++c) {
-        const int j = part * kCoarseCols + c;
-        if (on && j < nc && j >= row) {
-            G[(int64_t)row * nc + j] = a[c];
-            G[(int64_t)j * nc + row] = a[c];
+        for (int c = 0; c < CB; ++c) {
+            const int i = rb * RB + r, j = cb * CB + c;
+            double v = 0.0;
+            if (on && i < nc && j < nc) {
+                // the two triangles are assembled by different aggregates: their mean is used
+                v = 0.5 * (G[(int64_t)i * nc + j] + G[(int64_t)j * nc + i]);
+                const int ci = comp[i];
+                if (ci == comp[j] && enorm[ci] > 0.0) v += dmean * es[i] * es[j] / enorm[ci];
+                if (i == j && !(diag[i] > 0.0)) v = 1.0;   // dropped coarse function
+            }
+            a[r][c] = v;
         }
-    }
+    // every thread has read its entries of G before the first barrier of the inversion, and
+    // G is written only after the last one
+    gj_inverse_tiles<RB, CB, NRB, NCB>(a, nc, prow, fcol);
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            const int i = rb * RB + r, j = cb * CB + c;
+            if (on && i < nc && j < nc && j >= i) {
+                G[(int64_t)i * nc + j] = a[r][c];
+                G[(int64_t)j * nc + i] = a[r][c];
+            }
+        }
 }
 
 __global__ void k_fill_zero(double* __restrict__ p, int64_t n)
