@@ -542,7 +542,7 @@ template <int KG>
 struct PcgShared {
     float Binv[kBS * kBS];
     double crow[kCrowMax];          // rows of C0inv of the coarse functions of the touching aggregates
-    double r[kBS * KG];
+    float r[kBS * KG];              // the vector of the block product, rounded to FP32
     double rho[kCoarseMax * KG];    // coarse right-hand side [nc][KG] (and the block product's halves)
     double c[kMaxAggNbn * 4 * KG];  // coarse values [slot][4][KG]
     double wave[(kThreads / 64) * 4 * KG];
@@ -742,22 +742,24 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         const int cp = pub();
         if (t < kBS) {
 #pragma unroll
-            for (int c = 0; c < KG; ++c) S.r[t * KG + c] = (act && c < k) ? y[c] : 0.0;
+            for (int c = 0; c < KG; ++c) S.r[t * KG + c] = (act && c < k) ? (float)y[c] : 0.0f;
         }
         __syncthreads();
-        double v[KG];
+        // The block solve is a preconditioner: C_BB^{-1} (FP32) times y rounded to FP32, with
+        // FP32 sums (the solution's accuracy comes from the FP64 residuals; the CG iteration
+        // counts equal those of an FP64 product).  Padding rows of the block hold y = 0 and an
+        // identity block in C_BB^{-1}, so the product runs over all kBS rows with a fixed trip
+        // count.  Row tt's sum is split in two halves of j (owner: j < kBS / 2, helper
+        // tt + kBS: the rest), added in that order; chunks of CH rows: all LDS loads of a chunk
+        // are issued before its multiply-adds.
+        float v32[KG];
 #pragma unroll
-        for (int c = 0; c < KG; ++c) v[c] = 0.0;
-        // padding rows of the block hold y = 0 and an identity block in C_BB^{-1}, so the
-        // product runs over all kBS rows with a fixed trip count.  Row tt's sum is split in
-        // two halves of j (owner: j < kBS / 2, helper tt + kBS: the rest), added in that
-        // order; chunks of CH rows: all LDS loads of a chunk are issued before its FMAs.
+        for (int c = 0; c < KG; ++c) v32[c] = 0.0f;
         const int tt = t & (kBS - 1), jbeg = (t / kBS) * (kBS / 2);
         constexpr int CH = KG <= 3 ? 8 : (KG <= 6 ? 4 : 2);
 #pragma unroll 1
         for (int j0 = jbeg; j0 < jbeg + kBS / 2; j0 += CH) {
-            float bj[CH];
-            double yj[CH * KG];
+            float bj[CH], yj[CH * KG];
 #pragma unroll
             for (int q = 0; q < CH; ++q) bj[q] = S.Binv[(j0 + q) * kBS + tt];
 #pragma unroll
@@ -765,18 +767,17 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
 #pragma unroll
             for (int q = 0; q < CH; ++q)
 #pragma unroll
-                for (int c = 0; c < KG; ++c) v[c] += (double)bj[q] * yj[q * KG + c];
+                for (int c = 0; c < KG; ++c) v32[c] = __builtin_fmaf(bj[q], yj[q * KG + c], v32[c]);
         }
         // the helpers' halves go through S.rho, which is free until the block sums arrive
         if (t >= kBS) {
 #pragma unroll
-            for (int c = 0; c < KG; ++c) S.rho[tt * KG + c] = v[c];
+            for (int c = 0; c < KG; ++c) S.rho[tt * KG + c] = (double)v32[c];
         }
         __syncthreads();
-        if (t < kBS) {
+        double v[KG];
 #pragma unroll
-            for (int c = 0; c < KG; ++c) v[c] += S.rho[t * KG + c];
-        }
+        for (int c = 0; c < KG; ++c) v[c] = t < kBS ? (double)v32[c] + S.rho[t * KG + c] : 0.0;
         // the block's share of the coarse right-hand side: sum over its rows of phi[a] y
         double tmp[4 * KG];
 #pragma unroll
