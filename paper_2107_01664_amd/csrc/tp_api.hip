@@ -1,6 +1,6 @@
 // C-ABI of libtpsurf: validation, resident problem state and the host orchestration of
 // the hot path (energy, differential, fractional apply, preconditioner, descent step).
-#include "tp_internal.h"
+#include "tp_solver.h"
 
 #include <algorithm>
 #include <cmath>

@@ -21,7 +21,7 @@
 // lasts too long raises an abort flag and every workgroup leaves the loop.  All
 // workgroups add the per-workgroup partial sums in the same order, so they take the same
 // decisions and the result does not depend on scheduling.
-#include "tp_internal.h"
+#include "tp_solver.h"
 
 #include <algorithm>
 

@@ -27,7 +27,7 @@
 // 15 % more iterations and 1e-13 stalled it, while this form is unchanged up to 1e-13.)
 // Every solve ends by checking the true residual b - C x and restarts from it when the
 // recursively updated residual has drifted.
-#include "tp_internal.h"
+#include "tp_solver.h"
 
 #include <algorithm>
 #include <type_traits>
