@@ -516,7 +516,7 @@ struct PcgArgs {
     const int32_t* agg_of_block;
     const int32_t* abl_off;   // [nb + 1] aggregates touching each block (sorted, own included)
     const int32_t* abl;
-    const int8_t* rslot;      // [kPcgRowSlots][n]
+    const int8_t* rslot;      // [kPcgRowSlots][n], filled in order, -1 after the last
     const double* phi;        // [n][4]
     const double* rw;         // [kPcgRowSlots][4][n]
     const float* Binv;        // [nb][kBS][kBS], FP32
@@ -682,12 +682,16 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         cv[e] = in ? A.pval[(int64_t)e * n + i] : 0.0;
     }
     // the row's coarse functions and, per touched aggregate, the coarse part of its row of C
-    double phi[4], rwt[kPcgRowSlots][4];
-    int rsl[kPcgRowSlots];
+    // (slots beyond kPcgRegSlots, rare, are read from memory when used)
+    double phi[4], rwt[kPcgRegSlots][4];
+    int rsl[kPcgRegSlots];
+    int nq_row = 0;
+    if (act)
+        for (int q = 0; q < kPcgRowSlots; ++q) nq_row += A.rslot[(int64_t)q * n + i] >= 0 ? 1 : 0;
 #pragma unroll
     for (int a = 0; a < 4; ++a) phi[a] = act ? A.phi[i * 4 + a] : 0.0;
 #pragma unroll
-    for (int q = 0; q < kPcgRowSlots; ++q) {
+    for (int q = 0; q < kPcgRegSlots; ++q) {
         rsl[q] = act ? (int)A.rslot[(int64_t)q * n + i] : -1;
 #pragma unroll
         for (int a = 0; a < 4; ++a) rwt[q][a] = (rsl[q] >= 0) ? A.rw[((int64_t)q * 4 + a) * n + i] : 0.0;
@@ -876,13 +880,22 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
 #pragma unroll
                 for (int c = 0; c < KG; ++c) acc[c] += cv[e] * vnb[e][c];
 #pragma unroll
-            for (int q = 0; q < kPcgRowSlots; ++q)
+            for (int q = 0; q < kPcgRegSlots; ++q)
                 if (rsl[q] >= 0) {
 #pragma unroll
                     for (int a = 0; a < 4; ++a)
 #pragma unroll
                         for (int c = 0; c < KG; ++c) acc[c] += rwt[q][a] * S.c[(rsl[q] * 4 + a) * KG + c];
                 }
+            for (int q = kPcgRegSlots; q < nq_row; ++q) {   // slots are filled in order
+                const int sl = A.rslot[(int64_t)q * n + i];
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const double wq = A.rw[((int64_t)q * 4 + a) * n + i];
+#pragma unroll
+                    for (int c = 0; c < KG; ++c) acc[c] += wq * S.c[(sl * 4 + a) * KG + c];
+                }
+            }
             for (int e = kCache; e < A.ell_w; ++e) {   // (their coarse part is in rwt)
                 const int32_t j = A.pcol[(int64_t)e * n + i];
                 const double a = A.pval[(int64_t)e * n + i];

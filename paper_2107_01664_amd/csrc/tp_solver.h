@@ -32,7 +32,8 @@ hipError_t launch_cg(int64_t n, const int32_t* ecol, const double* eval, int ell
 // (component, Morton) order, dense block inverses in LDS; Galerkin coarse correction on
 // aggregates of consecutive blocks with four coarse functions each: an orthonormal basis of
 // {1, x, y, z} on the aggregate's vertices).
-constexpr int kPcgRowSlots = 4;          // neighbouring aggregates of one row, at most
+constexpr int kPcgRowSlots = 8;          // aggregates one row's entries reach, at most
+constexpr int kPcgRegSlots = 4;          // of them, kept in registers by the solver
 struct PcgSetup {
     int64_t n = 0;
     int nb = 0;

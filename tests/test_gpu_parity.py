@@ -312,12 +312,27 @@ def test_linked_tori_full_step(tp):
 
 # ------------------------------------------------- preconditioned vs plain Poisson solves
 
-@pytest.mark.parametrize("name", ["small_sphere", "linked_small", "tiny_tori"])
+# serving-mix meshes with one row whose entries reach five aggregates (more than the solver
+# keeps in registers)
+REQUEST_MESHES = {
+    "request_sphere": {"kind": "sphere", "freq": 11, "nF": 2420, "id": 29, "seed": 29, "steps": 4},
+    "request_torus": {"kind": "torus", "nu": 68, "nv": 34, "nF": 4624, "id": 19, "seed": 19, "steps": 4},
+}
+
+
+@pytest.mark.parametrize("name", ["small_sphere", "linked_small", "tiny_tori", "request_sphere",
+                                  "request_torus"])
 def test_pcg_matches_plain_cg(tp, meshes, name):
     """Two-level Schwarz preconditioned CG and plain CG reach the same per-component
     mean-zero solution; the preconditioned one in fewer iterations.  'tiny_tori' has
-    components smaller than one block (whole-component blocks)."""
-    m = mg.linked_tori(8, 6, 1.0, 0.25, 1.0) if name == "tiny_tori" else meshes[name]
+    components smaller than one block (whole-component blocks); the request meshes have a
+    row touching five aggregates, which must not send the solve to plain CG."""
+    if name == "tiny_tori":
+        m = mg.linked_tori(8, 6, 1.0, 0.25, 1.0)
+    elif name in REQUEST_MESHES:
+        m = mg.build_request_mesh(REQUEST_MESHES[name])
+    else:
+        m = meshes[name]
     b = mg.random_columns(m.nV, 3, 9)
     V, F = dev(m.V), dev(m.F, torch.int32)
     out = {}
@@ -331,6 +346,8 @@ def test_pcg_matches_plain_cg(tp, meshes, name):
         assert rel(out[pc][0], x0) <= 1e-5, (pc, rel(out[pc][0], x0))
     print(f"[pcg] {name}: iterations plain {out[0][1]} preconditioned {out[1][1]}", flush=True)
     assert out[1][1][0] <= out[0][1][0]
+    if name in REQUEST_MESHES:
+        assert out[1][1][0] <= 0.7 * out[0][1][0]
 
 
 @pytest.mark.parametrize("pc", [0, 1])
