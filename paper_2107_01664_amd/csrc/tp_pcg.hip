@@ -126,17 +126,14 @@ __device__ __forceinline__ void gj_inverse_tiles(double (&a)[RB][CB], int n, dou
     }
 }
 
-// Block inverses: one workgroup per block.
+// Inverse of block B by one workgroup of kInvThreads threads.
 constexpr int kInvThreads = 512;
-__global__ __launch_bounds__(kInvThreads) void k_block_inverse(int64_t n, int w, const int32_t* __restrict__ pcol,
-                                                       const double* __restrict__ pval,
-                                                       const int32_t* __restrict__ bstart,
-                                                       const int32_t* __restrict__ whole,
-                                                       float* __restrict__ Binv)
+__device__ __forceinline__ void block_inverse(int B, int64_t n, int w, const int32_t* __restrict__ pcol,
+                                              const double* __restrict__ pval, const int32_t* __restrict__ bstart,
+                                              const int32_t* __restrict__ whole, float* __restrict__ Binv)
 {
     extern __shared__ __align__(16) double A[];   // kBS x kBS, row-major
     __shared__ double prow[2 * kBS], fcol[2 * kBS];
-    const int B = blockIdx.x;
     const int32_t s0 = bstart[B], cnt = bstart[B + 1] - s0;
     for (int t = threadIdx.x; t < kBS * kBS; t += kInvThreads) A[t] = 0.0;
     __syncthreads();
@@ -415,9 +412,8 @@ static_assert(kMaxAggBlocks * kCoarseMax >= 4 * kMaxNbPcg, "aggregates of up to 
 // One workgroup: the regularised matrix is formed in registers (a tile per thread),
 // inverted there (gj_inverse_tiles) and written over G, each entry pair (i, j), (j, i)
 // from the upper triangle, so the result is exactly symmetric.
-__global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(int nc, const int32_t* __restrict__ acomp,
-                                                                 const double* __restrict__ esum,
-                                                                 double* __restrict__ G)
+__device__ __forceinline__ void coarse_inverse(int nc, const int32_t* __restrict__ acomp,
+                                               const double* __restrict__ esum, double* __restrict__ G)
 {
     __shared__ double prow[2 * kCoarseMax], fcol[2 * kCoarseMax];
     __shared__ double diag[kCoarseMax], es[kCoarseMax];
@@ -481,6 +477,21 @@ __global__ __launch_bounds__(kCoarseThreads) void k_coarse_inverse(int nc, const
                 G[(int64_t)j * nc + i] = a[r][c];
             }
         }
+}
+
+// The block inverses (workgroups 0 .. nb-1) and the coarse inverse (workgroup nb) in one
+// launch: they are independent, so the coarse inverse's single workgroup runs beside the
+// blocks' workgroups instead of after them.
+static_assert(kCoarseThreads == kInvThreads, "one workgroup size for both inverses");
+__global__ __launch_bounds__(kInvThreads) void k_inverses(int nb, int64_t n, int w, const int32_t* __restrict__ pcol,
+                                                          const double* __restrict__ pval,
+                                                          const int32_t* __restrict__ bstart,
+                                                          const int32_t* __restrict__ whole, float* __restrict__ Binv,
+                                                          int nc, const int32_t* __restrict__ acomp,
+                                                          const double* __restrict__ esum, double* __restrict__ G)
+{
+    if ((int)blockIdx.x < nb) block_inverse((int)blockIdx.x, n, w, pcol, pval, bstart, whole, Binv);
+    else coarse_inverse(nc, acomp, esum, G);
 }
 
 __global__ void k_fill_zero(double* __restrict__ p, int64_t n)
@@ -589,20 +600,26 @@ __device__ __forceinline__ double sum_fixed_x(const double* __restrict__ p, int 
     return (a[0] + a[1]) + (a[2] + a[3]);
 }
 
-// Dot product sum_i a[i] b[i * bstride] in the same fixed order.
+// Dot product sum_i a[i] b[i * bstride] in a fixed order: the loads of 8 terms at a time
+// are issued before they are added, term i to partial sum i % 4, and the partial sums are
+// added as (s0 + s1) + (s2 + s3).
 __device__ __forceinline__ double dot_fixed(const double* __restrict__ a, const double* __restrict__ b, int n,
                                             int bstride)
 {
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int i = 0;
-    for (; i + 4 <= n; i += 4) {
-        a0 += a[i] * b[i * bstride];
-        a1 += a[i + 1] * b[(i + 1) * bstride];
-        a2 += a[i + 2] * b[(i + 2) * bstride];
-        a3 += a[i + 3] * b[(i + 3) * bstride];
+    for (; i + 8 <= n; i += 8) {
+        double x[8], y[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            x[u] = a[i + u];
+            y[u] = b[(i + u) * bstride];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u & 3] += x[u] * y[u];
     }
-    for (; i < n; ++i) a0 += a[i] * b[i * bstride];
-    return (a0 + a1) + (a2 + a3);
+    for (; i < n; ++i) acc[i & 3] += a[i] * b[i * bstride];
+    return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // Fixed-order workgroup reduction of M values per thread (kThreads threads): butterfly
@@ -1087,13 +1104,7 @@ hipError_t launch_pcg_setup(const PcgSetup& ps, const double* V, const int32_t* 
                        ps.n, ps.ell_w, ps.perm, lap_off, lap_val, ps.pval);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t binv_smem = sizeof(double) * kBS * kBS;
-    e = hipFuncSetAttribute((const void*)k_block_inverse, hipFuncAttributeMaxDynamicSharedMemorySize, (int)binv_smem);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_block_inverse, dim3(ps.nb), dim3(kInvThreads), binv_smem, s, ps.n, ps.ell_w, ps.pcol,
-                       ps.pval, ps.bstart, ps.whole, ps.Binv);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    // coarse functions, their rows of C, the Galerkin matrix and its inverse
+    // coarse functions, their rows of C and the Galerkin matrix; then both inverses
     hipLaunchKernelGGL(k_agg_basis, dim3(ps.na), dim3(kAggThreads), 0, s, ps.perm, V, ps.astart, ps.bstart, ps.phi,
                        ps.esum);
     if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -1110,7 +1121,11 @@ hipError_t launch_pcg_setup(const PcgSetup& ps, const double* V, const int32_t* 
     hipLaunchKernelGGL(k_coarse_assemble, dim3(ps.na), dim3(kAggThreads), asm_smem, s, ps.n, ps.na, ps.nc,
                        ps.astart, ps.bstart, ps.blk, ps.abl_off, ps.abl, ps.rslot, ps.phi, ps.rw, ps.C0inv);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_coarse_inverse, dim3(1), dim3(kCoarseThreads), 0, s, ps.nc, ps.acomp, ps.esum, ps.C0inv);
+    const size_t binv_smem = sizeof(double) * kBS * kBS;
+    e = hipFuncSetAttribute((const void*)k_inverses, hipFuncAttributeMaxDynamicSharedMemorySize, (int)binv_smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_inverses, dim3(ps.nb + 1), dim3(kInvThreads), binv_smem, s, ps.nb, ps.n, ps.ell_w, ps.pcol,
+                       ps.pval, ps.bstart, ps.whole, ps.Binv, ps.nc, ps.acomp, ps.esum, ps.C0inv);
     return hipGetLastError();
 }
 
