@@ -28,7 +28,7 @@
 namespace tp {
 
 constexpr int kCgBlock = 256;
-constexpr int kMaxW = 128;           // workgroups per column group
+constexpr int kMaxW = 256;           // workgroups per column group
 static_assert(kMaxW <= kMaxBarrierW, "one barrier flag per workgroup");
 constexpr int kMaxGroups = 8;
 
