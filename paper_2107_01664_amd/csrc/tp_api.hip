@@ -235,6 +235,11 @@ struct tp_problem {
     DevBuf<int8_t> pcg_rslot, pcg_eslot;
     DevBuf<float> pcg_Binv;
     DevBuf<double> pcg_pval, pcg_phi, pcg_rw, pcg_esum, pcg_C0inv, pcg_Vb, pcg_rho, pcg_red, pcg_bp, pcg_xp;
+    // more blocks than one co-resident workgroup each: the multi-launch solve and its work
+    bool pcg_ml = false;
+    DevBuf<double> ml_r, ml_p, ml_s, ml_m, ml_an, ml_v, ml_shares, ml_g, ml_part;
+    DevBuf<char> ml_state;
+    HostBuf<char> ml_state_host;
     int64_t nnz = 0;
     int ncomp = 0;
 
@@ -289,6 +294,8 @@ struct tp_problem {
              pcg_rslot.bytes() + pcg_eslot.bytes() + pcg_phi.bytes() + pcg_rw.bytes() + pcg_esum.bytes() +
              pcg_Binv.bytes() + pcg_pval.bytes() + pcg_C0inv.bytes() + pcg_Vb.bytes() +
              pcg_rho.bytes() + pcg_red.bytes() + pcg_bp.bytes() + pcg_xp.bytes();
+        b += ml_r.bytes() + ml_p.bytes() + ml_s.bytes() + ml_m.bytes() + ml_an.bytes() + ml_v.bytes() +
+             ml_shares.bytes() + ml_g.bytes() + ml_part.bytes() + ml_state.bytes();
         b += part.bytes() + gface.bytes() + zbuf.bytes() + scal.bytes() + red.bytes() + vol6.bytes() +
              edge.bytes() + ub.bytes();
         b += cg_Z.bytes() + cg_p.bytes() + cg_red.bytes() + cg_relres.bytes() + cg_bar.bytes() +
@@ -514,7 +521,8 @@ tp_status build_pcg(tp_problem* P, const std::vector<int32_t>& label, int ncomp,
     const int nb = (int)bstart.size();
     bstart.push_back((int32_t)n);
     P->have_pcg = false;
-    if (nb < 1 || nb > pcg_max_blocks()) return TP_OK;        // too many blocks: plain CG
+    if (nb < 1 || nb > pcg_max_blocks_multi()) return TP_OK;  // too many blocks: plain CG
+    P->pcg_ml = nb > pcg_max_blocks();                        // multi-launch solve
     std::vector<int32_t> blk(n);
     for (int b = 0; b < nb; ++b)
         for (int32_t i = bstart[b]; i < bstart[b + 1]; ++i) blk[i] = b;
@@ -1045,11 +1053,21 @@ tp_status ensure_cg(tp_problem* P, int k)
     if (P->have_pcg) {
         const size_t n = (size_t)P->nV;
         const size_t kc = (size_t)std::min(k, kMaxGroupCols);
-        TP_TRY(P->pcg_Vb.ensure(2 * n * kc, s));
-        TP_TRY(P->pcg_rho.ensure((size_t)2 * P->pcg.nb * 4 * kc, s));
-        TP_TRY(P->pcg_red.ensure((size_t)2 * P->pcg.nb * 3 * kc, s));
         TP_TRY(P->pcg_bp.ensure(n * kc, s));
         TP_TRY(P->pcg_xp.ensure(n * kc, s));
+        if (!P->pcg_ml) {
+            TP_TRY(P->pcg_Vb.ensure(2 * n * kc, s));
+            TP_TRY(P->pcg_rho.ensure((size_t)2 * P->pcg.nb * 4 * kc, s));
+            TP_TRY(P->pcg_red.ensure((size_t)2 * P->pcg.nb * 3 * kc, s));
+        } else {
+            for (DevBuf<double>* v : {&P->ml_r, &P->ml_p, &P->ml_s, &P->ml_m, &P->ml_an, &P->ml_v})
+                TP_TRY(v->ensure(n * kc, s));
+            TP_TRY(P->ml_shares.ensure((size_t)P->pcg.nb * 4 * kMaxGroupCols, s));
+            TP_TRY(P->ml_g.ensure((size_t)P->pcg.nc * kMaxGroupCols, s));
+            TP_TRY(P->ml_part.ensure(pcg_ml_part_doubles(P->nV), s));
+            TP_TRY(P->ml_state.ensure(pcg_ml_state_bytes(), s));
+            TP_TRY(P->ml_state_host.ensure(pcg_ml_state_bytes()));
+        }
     }
     return TP_OK;
 }
@@ -1085,13 +1103,29 @@ tp_status enqueue_cg(const Batch& B, double* const* b, double* const* x, int k, 
 {
     if (B.empty()) return TP_OK;
     hipStream_t s = B[0]->stream;
-    std::vector<size_t> pc, plain;
+    std::vector<size_t> pc, ml, plain;
     for (size_t m = 0; m < B.size(); ++m) {
         tp_problem* P = B[m];
         TP_TRY(ensure_cotan(P));
         TP_TRY(ensure_cg(P, k));
         TP_HIP(launch_project_mean(b[m], k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
-        (P->have_pcg ? pc : plain).push_back(m);
+        if (P->have_pcg && P->pcg_ml) ml.push_back(m);
+        else (P->have_pcg ? pc : plain).push_back(m);
+    }
+    // multi-launch solves (one problem at a time; each call returns after its solve)
+    for (size_t m : ml) {
+        tp_problem* P = B[m];
+        PcgMlWork w;
+        w.r = P->ml_r.p; w.p = P->ml_p.p; w.s = P->ml_s.p; w.m = P->ml_m.p; w.an = P->ml_an.p; w.v = P->ml_v.p;
+        w.shares = P->ml_shares.p; w.g = P->ml_g.p; w.part = P->ml_part.p;
+        w.state = P->ml_state.p; w.state_host = P->ml_state_host.p;
+        for (int c0 = 0; c0 < k; c0 += kMaxGroupCols) {
+            const int kc = std::min(kMaxGroupCols, k - c0);
+            TP_HIP(launch_permute_rows(P->nV, kc, P->pcg.perm, k, c0, b[m], P->pcg_bp.p, true, s));
+            TP_HIP(launch_pcg_ml(P->pcg, P->pcg_bp.p, P->pcg_xp.p, kc, P->prm.cg_rtol, P->prm.cg_maxiter, w,
+                                 P->cg_iters.p + c0, P->cg_relres.p + c0, s));
+            TP_HIP(launch_permute_rows(P->nV, kc, P->pcg.perm, k, c0, P->pcg_xp.p, x[m], false, s));
+        }
     }
     if (!pc.empty()) {
         std::vector<PcgItem> items(pc.size());
@@ -1760,15 +1794,22 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
     // preconditioner
     if (prm.cg_precond) {
         const double nb = std::ceil(n / pcg_block_size()) + ncomp;
-        if (nb <= pcg_max_blocks()) {
+        if (nb <= pcg_max_blocks_multi()) {
             const double bs = pcg_block_size(), ncmax = pcg_max_coarse();
             // permutation, ELL pattern / values / entry slots, block and aggregate tables,
             // row slots, coarse functions and row weights, block inverses, coarse inverse
             b += 4 * n + 13 * n * w + 4 * 2 * (nb + 1) + 4 * nb * (4 + pcg_max_block_aggregates()) + 4 * n +
                  (4 + 32 + 8 * 4 * kPcgRowSlots) * n + 8 * ncmax + 4 * nb * bs * bs + 8 * ncmax * ncmax;
-            // solve work: two copies of the block solves, block shares of the coarse
-            // right-hand side and partial sums, permuted b and x
-            b += 8.0 * n * kMaxGroupCols * 4 + 8 * 2 * nb * 4 * kMaxGroupCols + 8 * 6 * nb * kMaxGroupCols;
+            if (nb <= pcg_max_blocks()) {
+                // solve work: two copies of the block solves, block shares of the coarse
+                // right-hand side and partial sums, permuted b and x
+                b += 8.0 * n * kMaxGroupCols * 4 + 8 * 2 * nb * 4 * kMaxGroupCols + 8 * 6 * nb * kMaxGroupCols;
+            } else {
+                // multi-launch work: six [n][k] vectors, permuted b and x, block shares, coarse
+                // right-hand side, per-workgroup partial sums, state
+                b += 8.0 * n * kMaxGroupCols * 8 + 8 * nb * 4 * kMaxGroupCols + 8 * ncmax * kMaxGroupCols +
+                     8.0 * (double)pcg_ml_part_doubles(nV) + (double)pcg_ml_state_bytes();
+            }
         }
     }
     // CG state and reductions

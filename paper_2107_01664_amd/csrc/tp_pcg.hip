@@ -42,6 +42,7 @@ constexpr int kMaxAggNbn = 16;      // aggregates touching a block (its own incl
 constexpr int kMaxNbPcg = 256;      // blocks (one co-resident workgroup per block)
 static_assert(kMaxNbPcg <= kMaxBarrierW, "one barrier flag per block");
 constexpr int kMaxAggBlocks = 7;    // blocks per aggregate: ceil(4 kMaxNbPcg / kCoarseMax)
+constexpr int kMaxNbMulti = 16384;  // blocks of the multi-launch solve (2,097,152 vertices)
 
 // ---------------------------------------------------------------- per-geometry setup
 
@@ -1218,6 +1219,491 @@ hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, v
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
+}
+
+
+// ---------------------------------------------------------------- multi-launch solve
+//
+// For problems with more blocks than workgroups that can be resident at once, the same
+// preconditioned Chronopoulos-Gear iteration runs as one kernel per phase; the kernel
+// boundaries are the grid-wide synchronisation.  Per iteration:
+//   k_ml_block       v = C_BB^{-1} r_B (FP32, as in k_pcg) and the block's shares Phi_B^T r
+//   k_ml_coarse_rhs  coarse right-hand side g: per aggregate, its blocks' shares in order
+//   k_ml_apply       coarse values of the aggregates of the workgroup's rows (rows of
+//                    C0^{-1} times g), m = v + Phi c
+//   k_ml_spmv        an = C m, partial sums of (r, m), (an, m), (r, r) per workgroup
+//   k_ml_scalars     the sums in fixed order, alpha and beta per column, the stop flag
+//   k_ml_update      p = m + beta p, s = an + beta s, x += alpha p, r -= alpha s
+// Every kernel returns at once when the stop flag is set, so a batch of iterations
+// enqueued past convergence costs only its launches; the host reads the flag after each
+// batch, then verifies with the true residual b - C x and restarts from it when needed.
+
+constexpr int kMlRows = kThreads;     // rows per workgroup of the row-parallel kernels
+constexpr int kMlBatch = 16;          // iterations enqueued between two reads of the flag
+constexpr int kMlScalarThreads = 1024;
+
+struct MlState {
+    int stop, total_it, first, have_bb;
+    int done[kMaxGroupCols], its[kMaxGroupCols];
+    double bb[kMaxGroupCols], rr[kMaxGroupCols], gam[kMaxGroupCols], alpha[kMaxGroupCols];
+    double ca[kMaxGroupCols], cb[kMaxGroupCols];   // this iteration's alpha, beta (0 when frozen)
+};
+
+__global__ void k_ml_init(MlState* st)
+{
+    if (threadIdx.x == 0) {
+        st->stop = 0;
+        st->total_it = 0;
+        st->first = 1;
+        st->have_bb = 0;
+        for (int c = 0; c < kMaxGroupCols; ++c) {
+            st->done[c] = 0;
+            st->its[c] = 0;
+            st->bb[c] = st->rr[c] = st->gam[c] = st->alpha[c] = st->ca[c] = st->cb[c] = 0.0;
+        }
+    }
+}
+
+// r = b - C x (x = 0 when zero_x: then r = b and x is cleared), p = s = 0, and per
+// workgroup the partial sums of r^2 (part[wg][0][c]).
+template <int KG>
+__global__ __launch_bounds__(kMlRows) void k_ml_residual(int64_t n, int k, int w, const int32_t* __restrict__ pcol,
+                                                         const double* __restrict__ pval, const double* __restrict__ b,
+                                                         double* __restrict__ x, double* __restrict__ r,
+                                                         double* __restrict__ p, double* __restrict__ s,
+                                                         double* __restrict__ part, int zero_x)
+{
+    __shared__ double wave_sh[(kMlRows / 64) * KG];
+    __shared__ double sums[KG];
+    const int64_t i = (int64_t)blockIdx.x * kMlRows + threadIdx.x;
+    double rr[KG];
+#pragma unroll
+    for (int c = 0; c < KG; ++c) rr[c] = 0.0;
+    if (i < n) {
+        double cx[KG];
+#pragma unroll
+        for (int c = 0; c < KG; ++c) cx[c] = 0.0;
+        if (!zero_x)
+            for (int e = 0; e < w; ++e) {
+                const int32_t j = pcol[(int64_t)e * n + i];
+                const double a = pval[(int64_t)e * n + i];
+#pragma unroll
+                for (int c = 0; c < KG; ++c)
+                    if (c < k) cx[c] += a * x[(int64_t)j * k + c];
+            }
+#pragma unroll
+        for (int c = 0; c < KG; ++c)
+            if (c < k) {
+                const int64_t id = i * k + c;
+                const double rv = b[id] - cx[c];
+                if (zero_x) x[id] = 0.0;   // (x is not read when zero_x)
+                r[id] = rv;
+                p[id] = 0.0;
+                s[id] = 0.0;
+                rr[c] = rv * rv;
+            }
+    }
+    wg_reduce<KG>(rr, wave_sh, sums);
+    if ((int)threadIdx.x < KG) part[(int64_t)blockIdx.x * 3 * KG + threadIdx.x] = sums[threadIdx.x];
+}
+
+template <int KG>
+__global__ __launch_bounds__(kThreads) void k_ml_block(const MlState* __restrict__ st, int k,
+                                                       const int32_t* __restrict__ bstart,
+                                                       const float* __restrict__ Binv, const double* __restrict__ phi,
+                                                       const double* __restrict__ r, double* __restrict__ v,
+                                                       double* __restrict__ shares)
+{
+    __shared__ float r32[kBS * KG];
+    __shared__ double half[kBS * KG];
+    __shared__ double wave_sh[(kThreads / 64) * 4 * KG];
+    __shared__ double sums[4 * KG];
+    if (st->stop) return;
+    const int B = blockIdx.x, t = threadIdx.x;
+    const int32_t s0 = bstart[B], cnt = bstart[B + 1] - s0;
+    const bool act = t < cnt;
+    const int64_t i = s0 + t;
+    double y[KG];
+#pragma unroll
+    for (int c = 0; c < KG; ++c) y[c] = (act && c < k) ? r[i * k + c] : 0.0;
+    if (t < kBS) {
+#pragma unroll
+        for (int c = 0; c < KG; ++c) r32[t * KG + c] = (float)y[c];
+    }
+    __syncthreads();
+    // the block product as in k_pcg: FP32, row tt's sum in two halves of j
+    const int tt = t & (kBS - 1), jbeg = (t / kBS) * (kBS / 2);
+    const float* Bi = Binv + (int64_t)B * kBS * kBS;
+    float v32[KG];
+#pragma unroll
+    for (int c = 0; c < KG; ++c) v32[c] = 0.0f;
+    constexpr int CH = 8;
+#pragma unroll 1
+    for (int j0 = jbeg; j0 < jbeg + kBS / 2; j0 += CH) {
+        float bj[CH], yj[CH * KG];
+#pragma unroll
+        for (int q = 0; q < CH; ++q) bj[q] = Bi[(j0 + q) * kBS + tt];
+#pragma unroll
+        for (int q = 0; q < CH * KG; ++q) yj[q] = r32[j0 * KG + q];
+#pragma unroll
+        for (int q = 0; q < CH; ++q)
+#pragma unroll
+            for (int c = 0; c < KG; ++c) v32[c] = __builtin_fmaf(bj[q], yj[q * KG + c], v32[c]);
+    }
+    if (t >= kBS) {
+#pragma unroll
+        for (int c = 0; c < KG; ++c) half[tt * KG + c] = (double)v32[c];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < KG; ++c)
+            if (c < k) v[i * k + c] = (double)v32[c] + half[t * KG + c];
+    }
+    double tmp[4 * KG];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const double ph = act ? phi[i * 4 + a] : 0.0;
+#pragma unroll
+        for (int c = 0; c < KG; ++c) tmp[a * KG + c] = ph * y[c];
+    }
+    wg_reduce<4 * KG>(tmp, wave_sh, sums);
+    if (t < 4 * KG) shares[(int64_t)B * 4 * KG + t] = sums[t];
+}
+
+// g[4 ag + a][c] = sum over the blocks of aggregate ag, in order, of their shares.
+template <int KG>
+__global__ __launch_bounds__(64) void k_ml_coarse_rhs(const MlState* __restrict__ st, const int32_t* __restrict__ astart,
+                                                      const double* __restrict__ shares, double* __restrict__ g)
+{
+    if (st->stop) return;
+    const int ag = blockIdx.x, t = threadIdx.x;
+    if (t >= 4 * KG) return;
+    const int b0 = astart[ag], b1 = astart[ag + 1];
+    double acc = 0.0;
+    for (int bb = b0; bb < b1; bb += 8) {
+        double u[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) u[q] = bb + q < b1 ? shares[(int64_t)(bb + q) * 4 * KG + t] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc += u[q];
+    }
+    g[(int64_t)ag * 4 * KG + t] = acc;
+}
+
+// Coarse values of the aggregates of rows [r0, r0 + kMlRows) (consecutive in block order),
+// then m = v + Phi c for those rows.
+template <int KG>
+__global__ __launch_bounds__(kMlRows) void k_ml_apply(const MlState* __restrict__ st, int64_t n, int nc, int k,
+                                                      const int32_t* __restrict__ blk,
+                                                      const int32_t* __restrict__ agg_of_block,
+                                                      const double* __restrict__ C0inv, const double* __restrict__ g,
+                                                      const double* __restrict__ phi, const double* __restrict__ v,
+                                                      double* __restrict__ m)
+{
+    __shared__ double gs[kCoarseMax * KG];
+    __shared__ double cw[kCoarseMax * KG];
+    __shared__ double psum[kMlRows];
+    if (st->stop) return;
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * kMlRows;
+    const int64_t r1 = min(n, r0 + kMlRows);
+    const int ag_lo = agg_of_block[blk[r0]], ag_hi = agg_of_block[blk[r1 - 1]];
+    for (int q = t; q < nc * KG; q += kMlRows) gs[q] = g[q];
+    __syncthreads();
+    const int jobs = (ag_hi - ag_lo + 1) * 4 * KG;
+    for (int j0 = 0; j0 < jobs; j0 += kMlRows) {
+        const int nj = min(kMlRows, jobs - j0);
+        const int P = max(1, kMlRows / nj);
+        const int chunk = (nc + P - 1) / P;
+        const int jl = t / P, pt = t - jl * P;
+        if (jl < nj) {
+            const int job = j0 + jl, row = job / KG, c = job - row * KG;
+            const int d = 4 * ag_lo + row;
+            const int d0 = pt * chunk, d1 = min(nc, d0 + chunk);
+            psum[jl * P + pt] = d1 > d0 ? dot_fixed(C0inv + (int64_t)d * nc + d0, gs + d0 * KG + c, d1 - d0, KG) : 0.0;
+        }
+        __syncthreads();
+        if (t < nj) cw[j0 + t] = sum_fixed(psum + t * P, P, 1);
+        __syncthreads();
+    }
+    const int64_t i = r0 + t;
+    if (i < n) {
+        const int ag = agg_of_block[blk[i]] - ag_lo;
+        double ph[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) ph[a] = phi[i * 4 + a];
+#pragma unroll
+        for (int c = 0; c < KG; ++c)
+            if (c < k) {
+                double cm = 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) cm += ph[a] * cw[(ag * 4 + a) * KG + c];
+                m[i * k + c] = v[i * k + c] + cm;
+            }
+    }
+}
+
+template <int KG>
+__global__ __launch_bounds__(kMlRows) void k_ml_spmv(const MlState* __restrict__ st, int64_t n, int k, int w,
+                                                     const int32_t* __restrict__ pcol, const double* __restrict__ pval,
+                                                     const double* __restrict__ m, const double* __restrict__ r,
+                                                     double* __restrict__ an, double* __restrict__ part)
+{
+    __shared__ double wave_sh[(kMlRows / 64) * 3 * KG];
+    __shared__ double sums[3 * KG];
+    if (st->stop) return;
+    const int64_t i = (int64_t)blockIdx.x * kMlRows + threadIdx.x;
+    double tmp[3 * KG];
+#pragma unroll
+    for (int q = 0; q < 3 * KG; ++q) tmp[q] = 0.0;
+    if (i < n) {
+        double acc[KG];
+#pragma unroll
+        for (int c = 0; c < KG; ++c) acc[c] = 0.0;
+        for (int e = 0; e < w; ++e) {
+            const int32_t j = pcol[(int64_t)e * n + i];
+            const double a = pval[(int64_t)e * n + i];
+#pragma unroll
+            for (int c = 0; c < KG; ++c)
+                if (c < k) acc[c] += a * m[(int64_t)j * k + c];
+        }
+#pragma unroll
+        for (int c = 0; c < KG; ++c)
+            if (c < k) {
+                const double mi = m[i * k + c], ri = r[i * k + c];
+                an[i * k + c] = acc[c];
+                tmp[c] = ri * mi;
+                tmp[KG + c] = acc[c] * mi;
+                tmp[2 * KG + c] = ri * ri;
+            }
+    }
+    wg_reduce<3 * KG>(tmp, wave_sh, sums);
+    if ((int)threadIdx.x < 3 * KG) part[(int64_t)blockIdx.x * 3 * KG + threadIdx.x] = sums[threadIdx.x];
+}
+
+// Sums over the nwg workgroups of the first M values of part ([nwg][3KG]) in a fixed
+// order (each value cut into P parts of consecutive workgroups, the parts added in order)
+// into tot[0 .. M), by kMlScalarThreads threads.
+template <int M, int KG>
+__device__ __forceinline__ void ml_grid_sum(const double* __restrict__ part, int nwg, double* ps, double* tot)
+{
+    constexpr int P = kMlScalarThreads / M;
+    const int t = threadIdx.x;
+    const int chunk = (nwg + P - 1) / P;
+    const int q = t / P, pt = t - q * P;
+    if (q < M) {
+        const int w0 = pt * chunk, w1 = min(nwg, w0 + chunk);
+        double acc = 0.0;
+        for (int ww = w0; ww < w1; ww += 8) {
+            double u[8];
+#pragma unroll
+            for (int z = 0; z < 8; ++z) u[z] = ww + z < w1 ? part[(int64_t)(ww + z) * 3 * KG + q] : 0.0;
+#pragma unroll
+            for (int z = 0; z < 8; ++z) acc += u[z];
+        }
+        ps[q * P + pt] = acc;
+    }
+    __syncthreads();
+    if (t < M) {
+        double a = 0.0;
+        for (int z = 0; z < P; ++z) a += ps[t * P + z];
+        tot[t] = a;
+    }
+    __syncthreads();
+}
+
+// The column scalars of one iteration (the rules of k_pcg): gamma = (r, m), delta =
+// (an, m), |r|^2; the first iteration of a solve takes |b|^2 from it; columns whose |r|^2
+// is at or below rtol^2 |b|^2 are frozen (alpha = beta = 0); the stop flag is raised when
+// no column is open or the iteration budget is spent.
+template <int KG>
+__global__ __launch_bounds__(kMlScalarThreads) void k_ml_scalars(MlState* __restrict__ st, const double* __restrict__ part,
+                                                                  int nwg, int k, double rtol2, int maxiter)
+{
+    __shared__ double ps[kMlScalarThreads];
+    __shared__ double tot[3 * KG];
+    __shared__ int live_sh[KG];
+    if (st->stop) return;
+    ml_grid_sum<3 * KG, KG>(part, nwg, ps, tot);
+    const int t = threadIdx.x;
+    const bool can = st->total_it < maxiter;
+    if (t < KG) {
+        const int c = t;
+        const double gm = tot[c], de = tot[KG + c], rrv = tot[2 * KG + c];
+        if (!st->have_bb) {
+            st->bb[c] = rrv;
+            st->done[c] = (c >= k || !(rrv > 0.0)) ? 1 : 0;
+        }
+        st->rr[c] = rrv;
+        const bool live = !st->done[c] && rrv > rtol2 * st->bb[c];
+        double al = 0.0, be = 0.0;
+        if (live) {
+            if (can) {
+                if (st->first) {
+                    al = gm / de;
+                } else {
+                    be = gm / st->gam[c];
+                    al = gm / (de - be * gm / st->alpha[c]);
+                }
+                st->its[c] = st->total_it + 1;
+            }
+            st->gam[c] = gm;
+            st->alpha[c] = al;
+        }
+        st->ca[c] = al;
+        st->cb[c] = be;
+        live_sh[c] = live ? 1 : 0;
+    }
+    __syncthreads();
+    if (t == 0) {
+        bool any = false;
+        for (int c = 0; c < KG; ++c) any = any || live_sh[c] != 0;
+        st->have_bb = 1;
+        if (!any || !can) {
+            st->stop = 1;
+        } else {
+            st->total_it += 1;
+            st->first = 0;
+        }
+    }
+}
+
+template <int KG>
+__global__ __launch_bounds__(kMlRows) void k_ml_update(const MlState* __restrict__ st, int64_t n, int k,
+                                                       const double* __restrict__ m, const double* __restrict__ an,
+                                                       double* __restrict__ p, double* __restrict__ s,
+                                                       double* __restrict__ x, double* __restrict__ r)
+{
+    if (st->stop) return;
+    const int64_t i = (int64_t)blockIdx.x * kMlRows + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int c = 0; c < KG; ++c)
+        if (c < k) {
+            const int64_t id = i * k + c;
+            const double al = st->ca[c], be = st->cb[c];
+            const double pn = m[id] + be * p[id];
+            const double sn = an[id] + be * s[id];
+            p[id] = pn;
+            s[id] = sn;
+            x[id] += al * pn;
+            r[id] -= al * sn;
+        }
+}
+
+// After a true residual (k_ml_residual): columns at or below rtol^2 |b|^2 are done; the
+// solve ends when all are done or the budget is spent, else it restarts from r (the stop
+// flag is lowered and the next iteration is a first one).
+template <int KG>
+__global__ __launch_bounds__(kMlScalarThreads) void k_ml_verify(MlState* __restrict__ st, const double* __restrict__ part,
+                                                                 int nwg, double rtol2, int maxiter)
+{
+    __shared__ double ps[kMlScalarThreads];
+    __shared__ double tot[KG];
+    ml_grid_sum<KG, KG>(part, nwg, ps, tot);
+    const int t = threadIdx.x;
+    if (t < KG && !st->done[t]) {
+        st->rr[t] = tot[t];
+        if (tot[t] <= rtol2 * st->bb[t]) st->done[t] = 1;
+    }
+    __syncthreads();
+    if (t == 0) {
+        bool all = true;
+        for (int c = 0; c < KG; ++c) all = all && st->done[c] != 0;
+        if (all || st->total_it >= maxiter) {
+            st->stop = 1;
+        } else {
+            st->stop = 0;
+            st->first = 1;
+        }
+    }
+}
+
+__global__ void k_ml_finish(const MlState* __restrict__ st, int k, int* __restrict__ iters, double* __restrict__ relres)
+{
+    const int c = threadIdx.x;
+    if (c < k) {
+        iters[c] = st->its[c];
+        relres[c] = st->bb[c] > 0.0 ? sqrt(st->rr[c] / st->bb[c]) : 0.0;
+    }
+}
+
+namespace {
+
+template <int KG>
+hipError_t launch_pcg_ml_k(const PcgSetup& ps, const double* b, double* x, int k, double rtol, int maxiter,
+                           const PcgMlWork& w, int* iters, double* relres, hipStream_t s)
+{
+    const int64_t n = ps.n;
+    const int nwg = (int)((n + kMlRows - 1) / kMlRows);
+    MlState* st = static_cast<MlState*>(w.state);
+    MlState* hs = static_cast<MlState*>(w.state_host);
+    const double rtol2 = rtol * rtol;
+    hipError_t e;
+#define TP_ML_CHECK() do { if ((e = hipGetLastError()) != hipSuccess) return e; } while (0)
+    hipLaunchKernelGGL(k_ml_init, dim3(1), dim3(64), 0, s, st);
+    TP_ML_CHECK();
+    hipLaunchKernelGGL((k_ml_residual<KG>), dim3(nwg), dim3(kMlRows), 0, s, n, k, ps.ell_w, ps.pcol, ps.pval, b, x,
+                       w.r, w.p, w.s, w.part, 1);
+    TP_ML_CHECK();
+    constexpr int kMaxRestarts = 6;
+    for (int cycle = 0;; ++cycle) {
+        for (;;) {
+            for (int q = 0; q < kMlBatch; ++q) {
+                hipLaunchKernelGGL((k_ml_block<KG>), dim3(ps.nb), dim3(kThreads), 0, s, st, k, ps.bstart, ps.Binv,
+                                   ps.phi, w.r, w.v, w.shares);
+                hipLaunchKernelGGL((k_ml_coarse_rhs<KG>), dim3(ps.na), dim3(64), 0, s, st, ps.astart, w.shares, w.g);
+                hipLaunchKernelGGL((k_ml_apply<KG>), dim3(nwg), dim3(kMlRows), 0, s, st, n, ps.nc, k, ps.blk,
+                                   ps.agg_of_block, ps.C0inv, w.g, ps.phi, w.v, w.m);
+                hipLaunchKernelGGL((k_ml_spmv<KG>), dim3(nwg), dim3(kMlRows), 0, s, st, n, k, ps.ell_w, ps.pcol,
+                                   ps.pval, w.m, w.r, w.an, w.part);
+                hipLaunchKernelGGL((k_ml_scalars<KG>), dim3(1), dim3(kMlScalarThreads), 0, s, st, w.part, nwg, k,
+                                   rtol2, maxiter);
+                hipLaunchKernelGGL((k_ml_update<KG>), dim3(nwg), dim3(kMlRows), 0, s, st, n, k, w.m, w.an, w.p, w.s,
+                                   x, w.r);
+            }
+            TP_ML_CHECK();
+            if ((e = hipMemcpyAsync(hs, st, sizeof(MlState), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+            if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+            if (hs->stop) break;
+        }
+        // true residual, then verification (and a restart from it when needed)
+        hipLaunchKernelGGL((k_ml_residual<KG>), dim3(nwg), dim3(kMlRows), 0, s, n, k, ps.ell_w, ps.pcol, ps.pval, b,
+                           x, w.r, w.p, w.s, w.part, 0);
+        hipLaunchKernelGGL((k_ml_verify<KG>), dim3(1), dim3(kMlScalarThreads), 0, s, st, w.part, nwg, rtol2, maxiter);
+        TP_ML_CHECK();
+        if ((e = hipMemcpyAsync(hs, st, sizeof(MlState), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        if (hs->stop || cycle >= kMaxRestarts) break;
+    }
+    hipLaunchKernelGGL(k_ml_finish, dim3(1), dim3(64), 0, s, st, k, iters, relres);
+    TP_ML_CHECK();
+#undef TP_ML_CHECK
+    return hipSuccess;
+}
+
+}  // namespace
+
+int pcg_max_blocks_multi() { return kMaxNbMulti; }
+size_t pcg_ml_state_bytes() { return sizeof(MlState); }
+size_t pcg_ml_part_doubles(int64_t n) { return (size_t)((n + kMlRows - 1) / kMlRows) * 3 * kMaxGroupCols; }
+
+hipError_t launch_pcg_ml(const PcgSetup& ps, const double* b, double* x, int k, double rtol, int maxiter,
+                         const PcgMlWork& w, int* iters, double* relres, hipStream_t s)
+{
+    switch (k) {
+    case 1: return launch_pcg_ml_k<1>(ps, b, x, k, rtol, maxiter, w, iters, relres, s);
+    case 2: return launch_pcg_ml_k<2>(ps, b, x, k, rtol, maxiter, w, iters, relres, s);
+    case 3: return launch_pcg_ml_k<3>(ps, b, x, k, rtol, maxiter, w, iters, relres, s);
+    case 4: return launch_pcg_ml_k<4>(ps, b, x, k, rtol, maxiter, w, iters, relres, s);
+    case 5: return launch_pcg_ml_k<5>(ps, b, x, k, rtol, maxiter, w, iters, relres, s);
+    case 6: return launch_pcg_ml_k<6>(ps, b, x, k, rtol, maxiter, w, iters, relres, s);
+    case 7: return launch_pcg_ml_k<7>(ps, b, x, k, rtol, maxiter, w, iters, relres, s);
+    case 8: return launch_pcg_ml_k<8>(ps, b, x, k, rtol, maxiter, w, iters, relres, s);
+    case 9: return launch_pcg_ml_k<9>(ps, b, x, k, rtol, maxiter, w, iters, relres, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 }  // namespace tp

@@ -97,6 +97,31 @@ size_t pcg_table_bytes(int n);
 hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, void* tab_host,
                             hipStream_t s);
 
+// Multi-launch form of the same solve for problems of more than pcg_max_blocks() blocks
+// (up to pcg_max_blocks_multi()): one kernel per phase of an iteration, the host reading
+// a device stop flag every few iterations (so the call returns after the solve has ended).
+// b, x in block order [n][k], k <= kMaxGroupCols; work arrays [n][k] (r, p, s, m, an, v),
+// shares [nb][4][kMaxGroupCols], g [nc][kMaxGroupCols], part pcg_ml_part_doubles(n),
+// state pcg_ml_state_bytes() on the device and in pinned host memory.
+struct PcgMlWork {
+    double* r = nullptr;
+    double* p = nullptr;
+    double* s = nullptr;
+    double* m = nullptr;
+    double* an = nullptr;
+    double* v = nullptr;
+    double* shares = nullptr;
+    double* g = nullptr;
+    double* part = nullptr;
+    void* state = nullptr;
+    void* state_host = nullptr;
+};
+int pcg_max_blocks_multi();
+size_t pcg_ml_state_bytes();
+size_t pcg_ml_part_doubles(int64_t n);
+hipError_t launch_pcg_ml(const PcgSetup& ps, const double* b, double* x, int k, double rtol, int maxiter,
+                         const PcgMlWork& w, int* iters, double* relres, hipStream_t s);
+
 // ------------------------------------------------------------------ device-side sync
 
 constexpr unsigned long long kSpinLimit = 1ull << 22;
