@@ -1307,28 +1307,28 @@ __global__ __launch_bounds__(kMlRows) void k_ml_residual(int64_t n, int k, int w
     if ((int)threadIdx.x < KG) part[(int64_t)blockIdx.x * 3 * KG + threadIdx.x] = sums[threadIdx.x];
 }
 
+// The block's rows of r are read and its rows of v written as one contiguous range (the
+// row stride is KG), staged through LDS.
 template <int KG>
-__global__ __launch_bounds__(kThreads) void k_ml_block(const MlState* __restrict__ st, int k,
+__global__ __launch_bounds__(kThreads) void k_ml_block(const MlState* __restrict__ st,
                                                        const int32_t* __restrict__ bstart,
                                                        const float* __restrict__ Binv, const double* __restrict__ phi,
                                                        const double* __restrict__ r, double* __restrict__ v,
                                                        double* __restrict__ shares)
 {
     __shared__ float r32[kBS * KG];
+    __shared__ double y64[kBS * KG];
     __shared__ double half[kBS * KG];
     __shared__ double wave_sh[(kThreads / 64) * 4 * KG];
     __shared__ double sums[4 * KG];
     if (st->stop) return;
     const int B = blockIdx.x, t = threadIdx.x;
     const int32_t s0 = bstart[B], cnt = bstart[B + 1] - s0;
-    const bool act = t < cnt;
-    const int64_t i = s0 + t;
-    double y[KG];
-#pragma unroll
-    for (int c = 0; c < KG; ++c) y[c] = (act && c < k) ? r[i * k + c] : 0.0;
-    if (t < kBS) {
-#pragma unroll
-        for (int c = 0; c < KG; ++c) r32[t * KG + c] = (float)y[c];
+    const double* rb = r + (int64_t)s0 * KG;
+    for (int e = t; e < kBS * KG; e += kThreads) {
+        const double yv = e < cnt * KG ? rb[e] : 0.0;
+        y64[e] = yv;
+        r32[e] = (float)yv;
     }
     __syncthreads();
     // the block product as in k_pcg: FP32, row tt's sum in two halves of j
@@ -1355,20 +1355,25 @@ __global__ __launch_bounds__(kThreads) void k_ml_block(const MlState* __restrict
         for (int c = 0; c < KG; ++c) half[tt * KG + c] = (double)v32[c];
     }
     __syncthreads();
-    if (act) {
+    if (t < kBS) {
 #pragma unroll
-        for (int c = 0; c < KG; ++c)
-            if (c < k) v[i * k + c] = (double)v32[c] + half[t * KG + c];
+        for (int c = 0; c < KG; ++c) half[t * KG + c] += (double)v32[c];   // own half + helper half
     }
+    // the block's shares of the coarse right-hand side: sum over its rows of phi[a] y
     double tmp[4 * KG];
+    {
+        const bool act = t < cnt;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const double ph = act ? phi[i * 4 + a] : 0.0;
+        for (int a = 0; a < 4; ++a) {
+            const double ph = act ? phi[(int64_t)(s0 + t) * 4 + a] : 0.0;
 #pragma unroll
-        for (int c = 0; c < KG; ++c) tmp[a * KG + c] = ph * y[c];
+            for (int c = 0; c < KG; ++c) tmp[a * KG + c] = act ? ph * y64[t * KG + c] : 0.0;
+        }
     }
-    wg_reduce<4 * KG>(tmp, wave_sh, sums);
+    wg_reduce<4 * KG>(tmp, wave_sh, sums);   // (its barriers also order the writes to half)
     if (t < 4 * KG) shares[(int64_t)B * 4 * KG + t] = sums[t];
+    double* vb = v + (int64_t)s0 * KG;
+    for (int e = t; e < cnt * KG; e += kThreads) vb[e] = half[e];
 }
 
 // g[4 ag + a][c] = sum over the blocks of aggregate ag, in order, of their shares.
@@ -1427,59 +1432,78 @@ __global__ __launch_bounds__(kMlRows) void k_ml_apply(const MlState* __restrict_
         if (t < nj) cw[j0 + t] = sum_fixed(psum + t * P, P, 1);
         __syncthreads();
     }
-    const int64_t i = r0 + t;
-    if (i < n) {
+    // element-wise over the rows' KG columns (contiguous loads and stores)
+    for (int64_t e = r0 * KG + t; e < r1 * KG; e += kMlRows) {
+        const int64_t i = e / KG;
+        const int c = (int)(e - i * KG);
         const int ag = agg_of_block[blk[i]] - ag_lo;
-        double ph[4];
+        double cm = 0.0;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) ph[a] = phi[i * 4 + a];
-#pragma unroll
-        for (int c = 0; c < KG; ++c)
-            if (c < k) {
-                double cm = 0.0;
-#pragma unroll
-                for (int a = 0; a < 4; ++a) cm += ph[a] * cw[(ag * 4 + a) * KG + c];
-                m[i * k + c] = v[i * k + c] + cm;
-            }
+        for (int a = 0; a < 4; ++a) cm += phi[i * 4 + a] * cw[(ag * 4 + a) * KG + c];
+        m[e] = v[e] + cm;
     }
 }
 
+// an = C m and the partial sums of (r, m), (an, m), (r, r): one thread per element (row,
+// column) of kMlSpRows rows, so the gathers of a row's KG values are contiguous across
+// lanes; the partial sums go through LDS and are added per column over the rows in order.
+constexpr int kMlSpThreads = 1024;
 template <int KG>
-__global__ __launch_bounds__(kMlRows) void k_ml_spmv(const MlState* __restrict__ st, int64_t n, int k, int w,
-                                                     const int32_t* __restrict__ pcol, const double* __restrict__ pval,
-                                                     const double* __restrict__ m, const double* __restrict__ r,
-                                                     double* __restrict__ an, double* __restrict__ part)
+constexpr int kMlSpRows() { return kMlSpThreads / KG; }
+template <int KG>
+__global__ __launch_bounds__(kMlSpThreads) void k_ml_spmv(const MlState* __restrict__ st, int64_t n, int w,
+                                                          const int32_t* __restrict__ pcol,
+                                                          const double* __restrict__ pval,
+                                                          const double* __restrict__ m, const double* __restrict__ r,
+                                                          double* __restrict__ an, double* __restrict__ part)
 {
-    __shared__ double wave_sh[(kMlRows / 64) * 3 * KG];
-    __shared__ double sums[3 * KG];
+    constexpr int R = kMlSpRows<KG>();
+    __shared__ double val[3][R * KG];
     if (st->stop) return;
-    const int64_t i = (int64_t)blockIdx.x * kMlRows + threadIdx.x;
-    double tmp[3 * KG];
-#pragma unroll
-    for (int q = 0; q < 3 * KG; ++q) tmp[q] = 0.0;
-    if (i < n) {
-        double acc[KG];
-#pragma unroll
-        for (int c = 0; c < KG; ++c) acc[c] = 0.0;
+    const int t = threadIdx.x;
+    const int64_t r0 = (int64_t)blockIdx.x * R;
+    const int rl = t / KG, c = t - rl * KG;
+    const int64_t i = r0 + rl;
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
+    if (rl < R && i < n) {
+        double acc = 0.0;
         for (int e = 0; e < w; ++e) {
             const int32_t j = pcol[(int64_t)e * n + i];
-            const double a = pval[(int64_t)e * n + i];
-#pragma unroll
-            for (int c = 0; c < KG; ++c)
-                if (c < k) acc[c] += a * m[(int64_t)j * k + c];
+            acc += pval[(int64_t)e * n + i] * m[(int64_t)j * KG + c];
         }
-#pragma unroll
-        for (int c = 0; c < KG; ++c)
-            if (c < k) {
-                const double mi = m[i * k + c], ri = r[i * k + c];
-                an[i * k + c] = acc[c];
-                tmp[c] = ri * mi;
-                tmp[KG + c] = acc[c] * mi;
-                tmp[2 * KG + c] = ri * ri;
-            }
+        const int64_t id = i * KG + c;
+        const double mi = m[id], ri = r[id];
+        an[id] = acc;
+        v0 = ri * mi;
+        v1 = acc * mi;
+        v2 = ri * ri;
     }
-    wg_reduce<3 * KG>(tmp, wave_sh, sums);
-    if ((int)threadIdx.x < 3 * KG) part[(int64_t)blockIdx.x * 3 * KG + threadIdx.x] = sums[threadIdx.x];
+    if (rl < R) {
+        val[0][t] = v0;
+        val[1][t] = v1;
+        val[2][t] = v2;
+    }
+    __syncthreads();
+    // each of the 3 KG sums over the R rows in P parts of consecutive rows, then the parts
+    // in order
+    constexpr int M = 3 * KG, P = kMlSpThreads / M, CH = (R + P - 1) / P;
+    __shared__ double ps[kMlSpThreads];
+    {
+        const int q = t / P, pt = t - q * P;
+        if (q < M) {
+            const int g = q / KG, cc = q - g * KG;
+            const int ro0 = pt * CH, ro1 = min(R, ro0 + CH);
+            double acc = 0.0;
+            for (int ro = ro0; ro < ro1; ++ro) acc += val[g][ro * KG + cc];
+            ps[q * P + pt] = acc;
+        }
+    }
+    __syncthreads();
+    if (t < M) {
+        double a = 0.0;
+        for (int z = 0; z < P; ++z) a += ps[t * P + z];
+        part[(int64_t)blockIdx.x * 3 * KG + t] = a;
+    }
 }
 
 // Sums over the nwg workgroups of the first M values of part ([nwg][3KG]) in a fixed
@@ -1569,27 +1593,30 @@ __global__ __launch_bounds__(kMlScalarThreads) void k_ml_scalars(MlState* __rest
     }
 }
 
+// Element-wise (the [n][KG] arrays as flat arrays, so a wave's loads are contiguous).
 template <int KG>
-__global__ __launch_bounds__(kMlRows) void k_ml_update(const MlState* __restrict__ st, int64_t n, int k,
+__global__ __launch_bounds__(kMlRows) void k_ml_update(const MlState* __restrict__ st, int64_t nk,
                                                        const double* __restrict__ m, const double* __restrict__ an,
                                                        double* __restrict__ p, double* __restrict__ s,
                                                        double* __restrict__ x, double* __restrict__ r)
 {
+    __shared__ double coef[2 * KG];
     if (st->stop) return;
-    const int64_t i = (int64_t)blockIdx.x * kMlRows + threadIdx.x;
-    if (i >= n) return;
-#pragma unroll
-    for (int c = 0; c < KG; ++c)
-        if (c < k) {
-            const int64_t id = i * k + c;
-            const double al = st->ca[c], be = st->cb[c];
-            const double pn = m[id] + be * p[id];
-            const double sn = an[id] + be * s[id];
-            p[id] = pn;
-            s[id] = sn;
-            x[id] += al * pn;
-            r[id] -= al * sn;
-        }
+    if ((int)threadIdx.x < KG) {
+        coef[threadIdx.x] = st->ca[threadIdx.x];
+        coef[KG + threadIdx.x] = st->cb[threadIdx.x];
+    }
+    __syncthreads();
+    const int64_t id = (int64_t)blockIdx.x * kMlRows + threadIdx.x;
+    if (id >= nk) return;
+    const int c = (int)(id % KG);
+    const double al = coef[c], be = coef[KG + c];
+    const double pn = m[id] + be * p[id];
+    const double sn = an[id] + be * s[id];
+    p[id] = pn;
+    s[id] = sn;
+    x[id] += al * pn;
+    r[id] -= al * sn;
 }
 
 // After a true residual (k_ml_residual): columns at or below rtol^2 |b|^2 are done; the
@@ -1637,6 +1664,9 @@ hipError_t launch_pcg_ml_k(const PcgSetup& ps, const double* b, double* x, int k
 {
     const int64_t n = ps.n;
     const int nwg = (int)((n + kMlRows - 1) / kMlRows);
+    const int nwk = (int)((n * KG + kMlRows - 1) / kMlRows);
+    const int nws = (int)((n + kMlSpRows<KG>() - 1) / kMlSpRows<KG>());
+    if (k != KG) return hipErrorInvalidValue;
     MlState* st = static_cast<MlState*>(w.state);
     MlState* hs = static_cast<MlState*>(w.state_host);
     const double rtol2 = rtol * rtol;
@@ -1651,17 +1681,17 @@ hipError_t launch_pcg_ml_k(const PcgSetup& ps, const double* b, double* x, int k
     for (int cycle = 0;; ++cycle) {
         for (;;) {
             for (int q = 0; q < kMlBatch; ++q) {
-                hipLaunchKernelGGL((k_ml_block<KG>), dim3(ps.nb), dim3(kThreads), 0, s, st, k, ps.bstart, ps.Binv,
+                hipLaunchKernelGGL((k_ml_block<KG>), dim3(ps.nb), dim3(kThreads), 0, s, st, ps.bstart, ps.Binv,
                                    ps.phi, w.r, w.v, w.shares);
                 hipLaunchKernelGGL((k_ml_coarse_rhs<KG>), dim3(ps.na), dim3(64), 0, s, st, ps.astart, w.shares, w.g);
                 hipLaunchKernelGGL((k_ml_apply<KG>), dim3(nwg), dim3(kMlRows), 0, s, st, n, ps.nc, k, ps.blk,
                                    ps.agg_of_block, ps.C0inv, w.g, ps.phi, w.v, w.m);
-                hipLaunchKernelGGL((k_ml_spmv<KG>), dim3(nwg), dim3(kMlRows), 0, s, st, n, k, ps.ell_w, ps.pcol,
+                hipLaunchKernelGGL((k_ml_spmv<KG>), dim3(nws), dim3(kMlSpThreads), 0, s, st, n, ps.ell_w, ps.pcol,
                                    ps.pval, w.m, w.r, w.an, w.part);
-                hipLaunchKernelGGL((k_ml_scalars<KG>), dim3(1), dim3(kMlScalarThreads), 0, s, st, w.part, nwg, k,
+                hipLaunchKernelGGL((k_ml_scalars<KG>), dim3(1), dim3(kMlScalarThreads), 0, s, st, w.part, nws, k,
                                    rtol2, maxiter);
-                hipLaunchKernelGGL((k_ml_update<KG>), dim3(nwg), dim3(kMlRows), 0, s, st, n, k, w.m, w.an, w.p, w.s,
-                                   x, w.r);
+                hipLaunchKernelGGL((k_ml_update<KG>), dim3(nwk), dim3(kMlRows), 0, s, st, n * KG, w.m, w.an, w.p,
+                                   w.s, x, w.r);
             }
             TP_ML_CHECK();
             if ((e = hipMemcpyAsync(hs, st, sizeof(MlState), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
@@ -1687,7 +1717,13 @@ hipError_t launch_pcg_ml_k(const PcgSetup& ps, const double* b, double* x, int k
 
 int pcg_max_blocks_multi() { return kMaxNbMulti; }
 size_t pcg_ml_state_bytes() { return sizeof(MlState); }
-size_t pcg_ml_part_doubles(int64_t n) { return (size_t)((n + kMlRows - 1) / kMlRows) * 3 * kMaxGroupCols; }
+// per-workgroup partial sums: the residual kernel's kMlRows rows per workgroup or the
+// sparse product's kMlSpRows, whichever gives more workgroups (the widest product)
+size_t pcg_ml_part_doubles(int64_t n)
+{
+    const int64_t rows = std::min<int64_t>(kMlRows, kMlSpRows<kMaxGroupCols>());
+    return (size_t)((n + rows - 1) / rows) * 3 * kMaxGroupCols;
+}
 
 hipError_t launch_pcg_ml(const PcgSetup& ps, const double* b, double* x, int k, double rtol, int maxiter,
                          const PcgMlWork& w, int* iters, double* relres, hipStream_t s)
