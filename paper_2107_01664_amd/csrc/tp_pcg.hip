@@ -1227,16 +1227,19 @@ hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, v
 // For problems with more blocks than workgroups that can be resident at once, the same
 // preconditioned Chronopoulos-Gear iteration runs as one kernel per phase; the kernel
 // boundaries are the grid-wide synchronisation.  Per iteration:
-//   k_ml_block       v = C_BB^{-1} r_B (FP32, as in k_pcg) and the block's shares Phi_B^T r
+//   k_ml_block       the previous iteration's update of the block's rows (p = m + beta p,
+//                    s = an + beta s, x += alpha p, r -= alpha s), then v = C_BB^{-1} r_B
+//                    (FP32, as in k_pcg) and the block's shares Phi_B^T r
 //   k_ml_coarse_rhs  coarse right-hand side g: per aggregate, its blocks' shares in order
 //   k_ml_apply       coarse values of the aggregates of the workgroup's rows (rows of
 //                    C0^{-1} times g), m = v + Phi c
 //   k_ml_spmv        an = C m, partial sums of (r, m), (an, m), (r, r) per workgroup
 //   k_ml_scalars     the sums in fixed order, alpha and beta per column, the stop flag
-//   k_ml_update      p = m + beta p, s = an + beta s, x += alpha p, r -= alpha s
 // Every kernel returns at once when the stop flag is set, so a batch of iterations
 // enqueued past convergence costs only its launches; the host reads the flag after each
 // batch, then verifies with the true residual b - C x and restarts from it when needed.
+// The update of an iteration that raised the stop flag is never applied: it has alpha = 0
+// in every column, so it would leave x and r as they are.
 
 constexpr int kMlRows = kThreads;     // rows per workgroup of the row-parallel kernels
 constexpr int kMlBatch = 16;          // iterations enqueued between two reads of the flag
@@ -1244,6 +1247,7 @@ constexpr int kMlScalarThreads = 1024;
 
 struct MlState {
     int stop, total_it, first, have_bb;
+    int upd;                                       // an update is pending (ca, cb)
     int done[kMaxGroupCols], its[kMaxGroupCols];
     double bb[kMaxGroupCols], rr[kMaxGroupCols], gam[kMaxGroupCols], alpha[kMaxGroupCols];
     double ca[kMaxGroupCols], cb[kMaxGroupCols];   // this iteration's alpha, beta (0 when frozen)
@@ -1256,6 +1260,7 @@ __global__ void k_ml_init(MlState* st)
         st->total_it = 0;
         st->first = 1;
         st->have_bb = 0;
+        st->upd = 0;
         for (int c = 0; c < kMaxGroupCols; ++c) {
             st->done[c] = 0;
             st->its[c] = 0;
@@ -1313,20 +1318,44 @@ template <int KG>
 __global__ __launch_bounds__(kThreads) void k_ml_block(const MlState* __restrict__ st,
                                                        const int32_t* __restrict__ bstart,
                                                        const float* __restrict__ Binv, const double* __restrict__ phi,
-                                                       const double* __restrict__ r, double* __restrict__ v,
-                                                       double* __restrict__ shares)
+                                                       const double* __restrict__ m, const double* __restrict__ an,
+                                                       double* __restrict__ p, double* __restrict__ s,
+                                                       double* __restrict__ x, double* __restrict__ r,
+                                                       double* __restrict__ v, double* __restrict__ shares)
 {
     __shared__ float r32[kBS * KG];
     __shared__ double y64[kBS * KG];
     __shared__ double half[kBS * KG];
     __shared__ double wave_sh[(kThreads / 64) * 4 * KG];
     __shared__ double sums[4 * KG];
+    __shared__ double coef[2 * KG];
     if (st->stop) return;
     const int B = blockIdx.x, t = threadIdx.x;
     const int32_t s0 = bstart[B], cnt = bstart[B + 1] - s0;
-    const double* rb = r + (int64_t)s0 * KG;
+    const bool upd = st->upd != 0;
+    if (t < KG) {
+        coef[t] = st->ca[t];
+        coef[KG + t] = st->cb[t];
+    }
+    __syncthreads();
+    const int64_t e0 = (int64_t)s0 * KG;
     for (int e = t; e < kBS * KG; e += kThreads) {
-        const double yv = e < cnt * KG ? rb[e] : 0.0;
+        double yv = 0.0;
+        if (e < cnt * KG) {
+            const int64_t id = e0 + e;
+            yv = r[id];
+            if (upd) {
+                const int c = e % KG;
+                const double al = coef[c], be = coef[KG + c];
+                const double pn = m[id] + be * p[id];
+                const double sn = an[id] + be * s[id];
+                p[id] = pn;
+                s[id] = sn;
+                x[id] += al * pn;
+                yv -= al * sn;
+                r[id] = yv;
+            }
+        }
         y64[e] = yv;
         r32[e] = (float)yv;
     }
@@ -1589,34 +1618,9 @@ __global__ __launch_bounds__(kMlScalarThreads) void k_ml_scalars(MlState* __rest
         } else {
             st->total_it += 1;
             st->first = 0;
+            st->upd = 1;
         }
     }
-}
-
-// Element-wise (the [n][KG] arrays as flat arrays, so a wave's loads are contiguous).
-template <int KG>
-__global__ __launch_bounds__(kMlRows) void k_ml_update(const MlState* __restrict__ st, int64_t nk,
-                                                       const double* __restrict__ m, const double* __restrict__ an,
-                                                       double* __restrict__ p, double* __restrict__ s,
-                                                       double* __restrict__ x, double* __restrict__ r)
-{
-    __shared__ double coef[2 * KG];
-    if (st->stop) return;
-    if ((int)threadIdx.x < KG) {
-        coef[threadIdx.x] = st->ca[threadIdx.x];
-        coef[KG + threadIdx.x] = st->cb[threadIdx.x];
-    }
-    __syncthreads();
-    const int64_t id = (int64_t)blockIdx.x * kMlRows + threadIdx.x;
-    if (id >= nk) return;
-    const int c = (int)(id % KG);
-    const double al = coef[c], be = coef[KG + c];
-    const double pn = m[id] + be * p[id];
-    const double sn = an[id] + be * s[id];
-    p[id] = pn;
-    s[id] = sn;
-    x[id] += al * pn;
-    r[id] -= al * sn;
 }
 
 // After a true residual (k_ml_residual): columns at or below rtol^2 |b|^2 are done; the
@@ -1638,6 +1642,7 @@ __global__ __launch_bounds__(kMlScalarThreads) void k_ml_verify(MlState* __restr
     if (t == 0) {
         bool all = true;
         for (int c = 0; c < KG; ++c) all = all && st->done[c] != 0;
+        st->upd = 0;
         if (all || st->total_it >= maxiter) {
             st->stop = 1;
         } else {
@@ -1664,7 +1669,6 @@ hipError_t launch_pcg_ml_k(const PcgSetup& ps, const double* b, double* x, int k
 {
     const int64_t n = ps.n;
     const int nwg = (int)((n + kMlRows - 1) / kMlRows);
-    const int nwk = (int)((n * KG + kMlRows - 1) / kMlRows);
     const int nws = (int)((n + kMlSpRows<KG>() - 1) / kMlSpRows<KG>());
     if (k != KG) return hipErrorInvalidValue;
     MlState* st = static_cast<MlState*>(w.state);
@@ -1682,7 +1686,7 @@ hipError_t launch_pcg_ml_k(const PcgSetup& ps, const double* b, double* x, int k
         for (;;) {
             for (int q = 0; q < kMlBatch; ++q) {
                 hipLaunchKernelGGL((k_ml_block<KG>), dim3(ps.nb), dim3(kThreads), 0, s, st, ps.bstart, ps.Binv,
-                                   ps.phi, w.r, w.v, w.shares);
+                                   ps.phi, w.m, w.an, w.p, w.s, x, w.r, w.v, w.shares);
                 hipLaunchKernelGGL((k_ml_coarse_rhs<KG>), dim3(ps.na), dim3(64), 0, s, st, ps.astart, w.shares, w.g);
                 hipLaunchKernelGGL((k_ml_apply<KG>), dim3(nwg), dim3(kMlRows), 0, s, st, n, ps.nc, k, ps.blk,
                                    ps.agg_of_block, ps.C0inv, w.g, ps.phi, w.v, w.m);
@@ -1690,8 +1694,6 @@ hipError_t launch_pcg_ml_k(const PcgSetup& ps, const double* b, double* x, int k
                                    ps.pval, w.m, w.r, w.an, w.part);
                 hipLaunchKernelGGL((k_ml_scalars<KG>), dim3(1), dim3(kMlScalarThreads), 0, s, st, w.part, nws, k,
                                    rtol2, maxiter);
-                hipLaunchKernelGGL((k_ml_update<KG>), dim3(nwk), dim3(kMlRows), 0, s, st, n * KG, w.m, w.an, w.p,
-                                   w.s, x, w.r);
             }
             TP_ML_CHECK();
             if ((e = hipMemcpyAsync(hs, st, sizeof(MlState), hipMemcpyDeviceToHost, s)) != hipSuccess) return e;
