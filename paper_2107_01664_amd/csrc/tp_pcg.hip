@@ -1474,38 +1474,42 @@ __global__ __launch_bounds__(kMlRows) void k_ml_apply(const MlState* __restrict_
 }
 
 // an = C m and the partial sums of (r, m), (an, m), (r, r): one thread per element (row,
-// column) of kMlSpRows rows, so the gathers of a row's KG values are contiguous across
+// column) of R = kMlSpThreads / KG rows at a time, `rounds` times (chosen at launch so
+// that there are about kMlSpTargetWg workgroups: enough to fill the device, few enough
+// partial sums for the scalars kernel), the gathers of a row's KG values contiguous across
 // lanes; the partial sums go through LDS and are added per column over the rows in order.
 constexpr int kMlSpThreads = 1024;
+constexpr int kMlSpTargetWg = 384;
+constexpr int kMlSpMaxRounds = 4;
 template <int KG>
-constexpr int kMlSpRows() { return kMlSpThreads / KG; }
-template <int KG>
-__global__ __launch_bounds__(kMlSpThreads) void k_ml_spmv(const MlState* __restrict__ st, int64_t n, int w,
+__global__ __launch_bounds__(kMlSpThreads) void k_ml_spmv(const MlState* __restrict__ st, int64_t n, int rounds, int w,
                                                           const int32_t* __restrict__ pcol,
                                                           const double* __restrict__ pval,
                                                           const double* __restrict__ m, const double* __restrict__ r,
                                                           double* __restrict__ an, double* __restrict__ part)
 {
-    constexpr int R = kMlSpRows<KG>();
+    constexpr int R = kMlSpThreads / KG;
     __shared__ double val[3][R * KG];
     if (st->stop) return;
     const int t = threadIdx.x;
-    const int64_t r0 = (int64_t)blockIdx.x * R;
+    const int64_t r0 = (int64_t)blockIdx.x * R * rounds;
     const int rl = t / KG, c = t - rl * KG;
-    const int64_t i = r0 + rl;
-    double v0 = 0.0, v1 = 0.0, v2 = 0.0;
-    if (rl < R && i < n) {
-        double acc = 0.0;
-        for (int e = 0; e < w; ++e) {
-            const int32_t j = pcol[(int64_t)e * n + i];
-            acc += pval[(int64_t)e * n + i] * m[(int64_t)j * KG + c];
+    double v0 = 0.0, v1 = 0.0, v2 = 0.0;   // this thread's column, its rows added in order
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int64_t i = r0 + (int64_t)rd * R + rl;
+        if (rl < R && i < n) {
+            double acc = 0.0;
+            for (int e = 0; e < w; ++e) {
+                const int32_t j = pcol[(int64_t)e * n + i];
+                acc += pval[(int64_t)e * n + i] * m[(int64_t)j * KG + c];
+            }
+            const int64_t id = i * KG + c;
+            const double mi = m[id], ri = r[id];
+            an[id] = acc;
+            v0 += ri * mi;
+            v1 += acc * mi;
+            v2 += ri * ri;
         }
-        const int64_t id = i * KG + c;
-        const double mi = m[id], ri = r[id];
-        an[id] = acc;
-        v0 = ri * mi;
-        v1 = acc * mi;
-        v2 = ri * ri;
     }
     if (rl < R) {
         val[0][t] = v0;
@@ -1669,7 +1673,10 @@ hipError_t launch_pcg_ml_k(const PcgSetup& ps, const double* b, double* x, int k
 {
     const int64_t n = ps.n;
     const int nwg = (int)((n + kMlRows - 1) / kMlRows);
-    const int nws = (int)((n + kMlSpRows<KG>() - 1) / kMlSpRows<KG>());
+    constexpr int kSpR = kMlSpThreads / KG;
+    const int sp_rounds = (int)std::max<int64_t>(1, std::min<int64_t>(kMlSpMaxRounds, (n + kSpR - 1) / kSpR / kMlSpTargetWg));
+    const int64_t sp_rows = (int64_t)kSpR * sp_rounds;
+    const int nws = (int)((n + sp_rows - 1) / sp_rows);
     if (k != KG) return hipErrorInvalidValue;
     MlState* st = static_cast<MlState*>(w.state);
     MlState* hs = static_cast<MlState*>(w.state_host);
@@ -1690,7 +1697,7 @@ hipError_t launch_pcg_ml_k(const PcgSetup& ps, const double* b, double* x, int k
                 hipLaunchKernelGGL((k_ml_coarse_rhs<KG>), dim3(ps.na), dim3(64), 0, s, st, ps.astart, w.shares, w.g);
                 hipLaunchKernelGGL((k_ml_apply<KG>), dim3(nwg), dim3(kMlRows), 0, s, st, n, ps.nc, k, ps.blk,
                                    ps.agg_of_block, ps.C0inv, w.g, ps.phi, w.v, w.m);
-                hipLaunchKernelGGL((k_ml_spmv<KG>), dim3(nws), dim3(kMlSpThreads), 0, s, st, n, ps.ell_w, ps.pcol,
+                hipLaunchKernelGGL((k_ml_spmv<KG>), dim3(nws), dim3(kMlSpThreads), 0, s, st, n, sp_rounds, ps.ell_w, ps.pcol,
                                    ps.pval, w.m, w.r, w.an, w.part);
                 hipLaunchKernelGGL((k_ml_scalars<KG>), dim3(1), dim3(kMlScalarThreads), 0, s, st, w.part, nws, k,
                                    rtol2, maxiter);
@@ -1720,10 +1727,10 @@ hipError_t launch_pcg_ml_k(const PcgSetup& ps, const double* b, double* x, int k
 int pcg_max_blocks_multi() { return kMaxNbMulti; }
 size_t pcg_ml_state_bytes() { return sizeof(MlState); }
 // per-workgroup partial sums: the residual kernel's kMlRows rows per workgroup or the
-// sparse product's kMlSpRows, whichever gives more workgroups (the widest product)
+// sparse product's one round of kMlSpThreads / KG rows, whichever gives more workgroups
 size_t pcg_ml_part_doubles(int64_t n)
 {
-    const int64_t rows = std::min<int64_t>(kMlRows, kMlSpRows<kMaxGroupCols>());
+    const int64_t rows = std::min<int64_t>(kMlRows, kMlSpThreads / kMaxGroupCols);
     return (size_t)((n + rows - 1) / rows) * 3 * kMaxGroupCols;
 }
 
