@@ -83,9 +83,34 @@ def parse():
                     help="precision and Barnes-Hut sweep (bumpy sphere, linked tori) instead of the step")
     ap.add_argument("--pairs-only", action="store_true",
                     help="time only the all-pairs launches of the step (for counter passes)")
+    ap.add_argument("--large-solve", action="store_true",
+                    help="time the preconditioned Poisson solve (9 columns) on a 163,842-vertex sphere, "
+                         "the multi-launch path, against plain CG")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 256 MiB device copy 5 times (counter calibration)")
     return ap.parse_args()
+
+
+def large_solve():
+    """The Poisson solve of the preconditioner on a mesh of more blocks than one
+    co-resident workgroup each: icosphere level 7 (163,842 vertices) with vertex noise 5e-4
+    (seed 1), 9 random columns (seed 2), solved twice (the second timed) with the
+    preconditioned and with plain CG."""
+    import torch
+    from paper_2107_01664_amd import meshgen as mg
+    from paper_2107_01664_amd import tpsurf as tp
+    m = mg.add_noise(mg.icosphere(7), 0.0005, 1)
+    V = torch.from_numpy(m.V).cuda()
+    F = torch.from_numpy(m.F).cuda()
+    b = torch.from_numpy(mg.random_columns(m.nV, 9, 2)).cuda()
+    out = {"large_solve": {"vertices": m.nV, "columns": 9}}
+    for pc in (1, 0):
+        with tp.Problem(V, F, tp.default_params(cg_precond=pc)) as P:
+            for _ in range(2):
+                _, r = P.poisson_solve(b)
+        out["large_solve"]["preconditioned" if pc else "plain"] = {
+            "iterations": int(r.cg_iters[0]), "relres": float(r.cg_relres[0]), "ms": float(r.t_ms[0])}
+    print(json.dumps(out), flush=True)
 
 
 def copy_probe():
@@ -320,6 +345,9 @@ def main():
         sys.exit(1)
     if a.copy_probe:
         copy_probe()
+        return
+    if a.large_solve:
+        large_solve()
         return
     if a.sweep:
         print(json.dumps(sweep()), flush=True)
