@@ -1428,7 +1428,7 @@ __global__ __launch_bounds__(64) void k_ml_coarse_rhs(const MlState* __restrict_
 // Coarse values of the aggregates of rows [r0, r0 + kMlRows) (consecutive in block order),
 // then m = v + Phi c for those rows.
 template <int KG>
-__global__ __launch_bounds__(kMlRows) void k_ml_apply(const MlState* __restrict__ st, int64_t n, int nc, int k,
+__global__ __launch_bounds__(kMlRows) void k_ml_apply(const MlState* __restrict__ st, int64_t n, int nc,
                                                       const int32_t* __restrict__ blk,
                                                       const int32_t* __restrict__ agg_of_block,
                                                       const double* __restrict__ C0inv, const double* __restrict__ g,
@@ -1695,7 +1695,7 @@ hipError_t launch_pcg_ml_k(const PcgSetup& ps, const double* b, double* x, int k
                 hipLaunchKernelGGL((k_ml_block<KG>), dim3(ps.nb), dim3(kThreads), 0, s, st, ps.bstart, ps.Binv,
                                    ps.phi, w.m, w.an, w.p, w.s, x, w.r, w.v, w.shares);
                 hipLaunchKernelGGL((k_ml_coarse_rhs<KG>), dim3(ps.na), dim3(64), 0, s, st, ps.astart, w.shares, w.g);
-                hipLaunchKernelGGL((k_ml_apply<KG>), dim3(nwg), dim3(kMlRows), 0, s, st, n, ps.nc, k, ps.blk,
+                hipLaunchKernelGGL((k_ml_apply<KG>), dim3(nwg), dim3(kMlRows), 0, s, st, n, ps.nc, ps.blk,
                                    ps.agg_of_block, ps.C0inv, w.g, ps.phi, w.v, w.m);
                 hipLaunchKernelGGL((k_ml_spmv<KG>), dim3(nws), dim3(kMlSpThreads), 0, s, st, n, sp_rounds, ps.ell_w, ps.pcol,
                                    ps.pval, w.m, w.r, w.an, w.part);
