@@ -818,16 +818,22 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         if (!sync()) return false;
         const double* Vb = vbuf(cp);
         const double* rho = rhob(cp);
-        // the neighbours' block solves are loaded now, so that their latency overlaps the
-        // block sums' load and the coarse values
+        // the neighbours' block solves: for up to 5 columns loaded now, so that their latency
+        // overlaps the block sums' load and the coarse values; with more, after the block
+        // sums (their kCache x KG loads would otherwise hold up the block sums' loads, which
+        // return in order behind them), overlapping the coarse values
         double vnb[kCache][KG];
-        if (act) {
+        auto load_vnb = [&]() {
+            if (act) {
 #pragma unroll
-            for (int e = 0; e < kCache; ++e)
+                for (int e = 0; e < kCache; ++e)
 #pragma unroll
-                for (int c = 0; c < KG; ++c)
-                    vnb[e][c] = (e < A.ell_w && c < k) ? xload(Vb + (int64_t)cj[e] * k + c) : 0.0;
-        }
+                    for (int c = 0; c < KG; ++c)
+                        vnb[e][c] = (e < A.ell_w && c < k) ? xload(Vb + (int64_t)cj[e] * k + c) : 0.0;
+            }
+        };
+        constexpr bool kVnbEarly = KG <= 5;
+        if (kVnbEarly) load_vnb();
         // coarse right-hand side [nc][KG]: function 4g + a sums the shares of aggregate g's
         // blocks in block order.  Jobs q = t + jj kThreads of this thread: the loads of kJB
         // jobs (all of them for up to 3 columns; 2 at a time for more, to bound the registers
@@ -864,6 +870,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
             }
         }
         __syncthreads();
+        if (!kVnbEarly) load_vnb();
         // coarse values S.c[sl][a][c] = sum_d C0inv[4 nbl[sl] + a][d] rho[d][c] for the
         // nsl x 4 x KG jobs: each job's dot product is cut into P parts (one per thread)
         const int jobs = nsl * 4 * KG;
