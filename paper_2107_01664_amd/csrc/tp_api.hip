@@ -242,6 +242,7 @@ struct tp_problem {
     HostBuf<char> ml_state_host;
     int64_t nnz = 0;
     int ncomp = 0;
+    int last_iters = 0;              // iterations of the problem's last solve (launch grouping)
 
     double area0 = 0, vol0 = 0, mean_edge = 0;
 
@@ -1128,6 +1129,15 @@ tp_status enqueue_cg(const Batch& B, double* const* b, double* const* x, int k, 
         }
     }
     if (!pc.empty()) {
+        // the problems are grouped into cooperative launches in this order and each launch
+        // lasts as long as its slowest problem: order them by their last solve's iteration
+        // count (then by size), so that problems of like length share a launch
+        std::stable_sort(pc.begin(), pc.end(), [&](size_t a, size_t b) {
+            const tp_problem* A = B[a];
+            const tp_problem* Q = B[b];
+            if (A->last_iters != Q->last_iters) return A->last_iters > Q->last_iters;
+            return A->pcg.nb > Q->pcg.nb;
+        });
         std::vector<PcgItem> items(pc.size());
         for (int c0 = 0; c0 < k; c0 += kMaxGroupCols) {
             const int kc = std::min(kMaxGroupCols, k - c0);
@@ -1188,6 +1198,7 @@ tp_status cg_result(tp_problem* P, int k, int which, int* it_max, double* res_ma
     }
     *it_max = im;
     *res_max = rm;
+    P->last_iters = im;
     // the solvers test |r|^2 <= rtol^2 |b|^2; the reported sqrt may round one ulp above rtol
     if (!(rm <= P->prm.cg_rtol * (1.0 + 1e-12)))
         return fail(TP_E_NOT_CONVERGED, "CG did not reach cg_rtol within cg_maxiter (relres " + std::to_string(rm) + ")");
