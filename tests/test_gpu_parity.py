@@ -375,7 +375,7 @@ def sphere41k():
     return mg.add_noise(mg.icosphere(6), 0.001, 1)
 
 
-@pytest.mark.parametrize("k", [3, 9])
+@pytest.mark.parametrize("k", [1, 3, 9])
 def test_pcg_multi_launch_sphere41k(tp, sphere41k, k):
     """More blocks (321) than workgroups resident at once: the preconditioned solve runs as
     one launch per phase.  Its solution meets 1e-10 in the true residual recomputed with the
@@ -400,6 +400,23 @@ def test_pcg_multi_launch_sphere41k(tp, sphere41k, k):
             assert r.max() <= 2e-10, r
             assert np.abs(O.project_mean_zero(xs, labels) - xs).max() <= 1e-12 * np.abs(xs).max()
     assert its[1] <= 0.4 * its[0], its
+
+
+def test_pcg_multi_launch_iteration_cap(tp, sphere41k):
+    """The multi-launch solve stops at the iteration budget (also across its batches of
+    iterations and its restarts): the status is 'not converged' and the report counts the
+    budget, for a budget inside the first batch and one across several."""
+    m = sphere41k
+    b = dev(mg.random_columns(m.nV, 2, 0))
+    for cap in (5, 37):
+        with tp.Problem(dev(m.V), dev(m.F, torch.int32), tp.default_params(cg_maxiter=cap)) as P:
+            with pytest.raises(tp.TpError) as e:
+                P.poisson_solve(b)
+            assert e.value.status == 5
+            x, rep = P.poisson_solve(b, allow_not_converged=True)
+        assert rep.cg_iters[0] == cap
+        assert 1e-10 < rep.cg_relres[0] < 1.0
+        assert torch.isfinite(x).all()
 
 
 def test_pcg_multi_launch_two_components(tp):
