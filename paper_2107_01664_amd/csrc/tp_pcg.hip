@@ -546,6 +546,7 @@ struct PcgArgs {
     int maxiter;
     int k;
     int block0;               // first workgroup of this problem in its launch
+    int stage;                // the block shares fit the LDS staging area after PcgShared
 };
 
 constexpr int kCrowMax = 7680;      // doubles of cached coarse-inverse rows (60 KB)
@@ -652,6 +653,8 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
 {
     extern __shared__ __align__(16) char smem_raw[];
     PcgShared<KG>& S = *reinterpret_cast<PcgShared<KG>*>(smem_raw);
+    // staging area for all blocks' coarse shares ([nb][4][k]), when the launch has room
+    double* stg = reinterpret_cast<double*>(smem_raw + (sizeof(PcgShared<KG>) + 15) / 16 * 16);
     int pm = 0;
     for (int q = 1; q < ntab; ++q)
         if ((int)blockIdx.x >= tab[q].block0) pm = q;
@@ -834,6 +837,29 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         };
         constexpr bool kVnbEarly = KG <= 5;
         if (kVnbEarly) load_vnb();
+        if (A.stage) {
+            // all blocks' shares in one contiguous, coalesced pass into LDS, then function
+            // 4g + a of the coarse right-hand side sums aggregate g's blocks in block order
+            // (the same sums, in the same order, as below)
+            const int tot = nb * 4 * k;
+            for (int e0 = t; e0 < tot; e0 += 8 * kThreads) {   // 8 loads in flight per thread
+                double u8[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) u8[u] = e0 + u * kThreads < tot ? xload(rho + e0 + u * kThreads) : 0.0;
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (e0 + u * kThreads < tot) stg[e0 + u * kThreads] = u8[u];
+            }
+            __syncthreads();
+            for (int q = t; q < nc * KG; q += kThreads) {
+                const int d = q / KG, c = q - d * KG, g = d / 4, a = d - 4 * g;
+                double acc = 0.0;
+                if (c < k)
+                    for (int bb = S.ast[g]; bb < S.ast[g + 1]; ++bb) acc += stg[(bb * 4 + a) * k + c];
+                S.rho[q] = acc;
+            }
+            __syncthreads();
+        } else {
         // coarse right-hand side [nc][KG]: function 4g + a sums the shares of aggregate g's
         // blocks in block order.  Jobs q = t + jj kThreads of this thread: the loads of kJB
         // jobs (all of them for up to 3 columns; 2 at a time for more, to bound the registers
@@ -870,6 +896,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
             }
         }
         __syncthreads();
+        }
         if (!kVnbEarly) load_vnb();
         // coarse values S.c[sl][a][c] = sum_d C0inv[4 nbl[sl] + a][d] rho[d][c] for the
         // nsl x 4 x KG jobs: each job's dot product is cut into P parts (one per thread)
@@ -1177,7 +1204,17 @@ hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, v
     if (n < 1) return hipSuccess;
     const void* fn = pcg_fn(k);
     if (!fn) return hipErrorInvalidValue;
-    const size_t smem = pcg_smem_bytes(k);
+    // LDS staging of the block shares when the largest problem's fit beside PcgShared
+    hipError_t e0;
+    int nb_max = 0;
+    for (int m = 0; m < n; ++m) nb_max = std::max(nb_max, items[m].ps->nb);
+    const size_t base = (pcg_smem_bytes(k) + 15) / 16 * 16;
+    const size_t stage_bytes = sizeof(double) * (size_t)nb_max * 4 * (size_t)k;
+    int lds_max = 0;
+    e0 = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device_info().device);
+    if (e0 != hipSuccess) return e0;
+    const bool stage = base + stage_bytes <= (size_t)lds_max;
+    const size_t smem = stage ? base + stage_bytes : pcg_smem_bytes(k);
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     int per_cu = 0;
@@ -1194,7 +1231,7 @@ hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, v
         a.abl = ps.abl; a.rslot = ps.rslot; a.phi = ps.phi; a.rw = ps.rw; a.Binv = ps.Binv; a.C0inv = ps.C0inv;
         a.b = it.b; a.x = it.x; a.Vb = it.w.Vb; a.rho = it.w.rho; a.red = it.w.red; a.bar = it.w.bar;
         a.iters = it.w.iters; a.relres = it.w.relres; a.flags = it.w.flags;
-        a.rtol = it.rtol; a.maxiter = it.maxiter; a.k = k; a.block0 = 0;
+        a.rtol = it.rtol; a.maxiter = it.maxiter; a.k = k; a.block0 = 0; a.stage = stage ? 1 : 0;
         if ((int64_t)ps.nb > cap) return hipErrorCooperativeLaunchTooLarge;
     }
     // launches of consecutive problems whose workgroups are resident together
