@@ -549,12 +549,13 @@ struct PcgArgs {
     int stage;                // the block shares fit the LDS staging area after PcgShared
 };
 
-constexpr int kCrowMax = 7680;      // doubles of cached coarse-inverse rows (60 KB)
+constexpr int kCrowMax = 7680;      // cached coarse-inverse entries (FP32: 30 KB)
 
 template <int KG>
 struct PcgShared {
     float Binv[kBS * kBS];
-    double crow[kCrowMax];          // rows of C0inv of the coarse functions of the touching aggregates
+    float crow[kCrowMax];           // rows of C0inv of the coarse functions of the touching
+                                    // aggregates, rounded to FP32 (as the block inverses are)
     float r[kBS * KG];              // the vector of the block product, rounded to FP32
     double rho[kCoarseMax * KG];    // coarse right-hand side [nc][KG] (and the block product's halves)
     double c[kMaxAggNbn * 4 * KG];  // coarse values [slot][4][KG]
@@ -605,22 +606,25 @@ __device__ __forceinline__ double sum_fixed_x(const double* __restrict__ p, int 
 // Dot product sum_i a[i] b[i * bstride] in a fixed order: the loads of 8 terms at a time
 // are issued before they are added, term i to partial sum i % 4, and the partial sums are
 // added as (s0 + s1) + (s2 + s3).
-__device__ __forceinline__ double dot_fixed(const double* __restrict__ a, const double* __restrict__ b, int n,
+template <class TA, bool ROUND32 = false>
+__device__ __forceinline__ double dot_fixed(const TA* __restrict__ a, const double* __restrict__ b, int n,
                                             int bstride)
 {
+    // the terms a[i] b[i], with a[i] rounded to FP32 first when ROUND32
+    auto av = [&](int i) -> double { return ROUND32 ? (double)(float)a[i] : (double)a[i]; };
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     int i = 0;
     for (; i + 8 <= n; i += 8) {
         double x[8], y[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            x[u] = a[i + u];
+            x[u] = av(i + u);
             y[u] = b[(i + u) * bstride];
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc[u & 3] += x[u] * y[u];
     }
-    for (; i < n; ++i) acc[i & 3] += a[i] * b[i * bstride];
+    for (; i < n; ++i) acc[i & 3] += av(i) * b[i * bstride];
     return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
@@ -683,7 +687,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
     if (crow_lds)
         for (int q = t; q < nsl * 4 * nc; q += kThreads) {
             const int row = q / nc;   // slot * 4 + function
-            S.crow[q] = A.C0inv[(int64_t)(4 * S.nbl[row / 4] + row % 4) * nc + (q % nc)];
+            S.crow[q] = (float)A.C0inv[(int64_t)(4 * S.nbl[row / 4] + row % 4) * nc + (q % nc)];
         }
     __syncthreads();
     int own_slot = 0;
@@ -908,10 +912,18 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
             const int jl = t / P, part = t - jl * P;
             if (jl < nj) {
                 const int job = j0 + jl, row = job / KG, c = job - row * KG;   // row = slot * 4 + a
-                const double* crow = crow_lds ? S.crow + (int64_t)row * nc
-                                              : A.C0inv + (int64_t)(4 * S.nbl[row / 4] + row % 4) * nc;
                 const int d0 = part * chunk, d1 = min(nc, d0 + chunk);
-                S.part[jl * P + part] = d1 > d0 ? dot_fixed(crow + d0, S.rho + d0 * KG + c, d1 - d0, KG) : 0.0;
+                double pv = 0.0;
+                if (d1 > d0) {
+                    // the coarse-inverse entries in FP32 either way (the same operator for
+                    // every block, whether its rows are cached in LDS or read from memory)
+                    if (crow_lds)
+                        pv = dot_fixed(S.crow + (int64_t)row * nc + d0, S.rho + d0 * KG + c, d1 - d0, KG);
+                    else
+                        pv = dot_fixed<double, true>(A.C0inv + (int64_t)(4 * S.nbl[row / 4] + row % 4) * nc + d0,
+                                                     S.rho + d0 * KG + c, d1 - d0, KG);
+                }
+                S.part[jl * P + part] = pv;
             }
             __syncthreads();
             if (t < nj) S.c[j0 + t] = sum_fixed(S.part + t * P, P, 1);
