@@ -49,6 +49,11 @@ def lib():
         L.tpo_gradient_rowlist.argtypes = [_dp, i64, _ip, i64, d, d, _lp, i64, _dp, _dp]
         L.tpo_fractional_rowlist.argtypes = [_dp, i64, _ip, i64, d, _dp, ctypes.c_int, _lp, i64, _dp]
         L.tpo_fractional_gather.argtypes = [_ip, i64, i64, _dp, ctypes.c_int, _dp]
+        L.tpo_face_gradients.argtypes = [_dp, _ip, i64, _dp, ctypes.c_int, _dp]
+        L.tpo_sobolev_rowlist.argtypes = [_dp, i64, _ip, i64, d, _dp, ctypes.c_int, _lp, i64, _dp]
+        L.tpo_sobolev_gather.argtypes = [_dp, _ip, i64, i64, _dp, ctypes.c_int, _dp]
+        L.tpo_sobolev_apply.argtypes = [_dp, i64, _ip, i64, d, _dp, ctypes.c_int, _dp]
+        L.tpo_sobolev_apply.restype = ctypes.c_int
         L.tpo_bh_frozen.argtypes = [_dp, _dp, i64, _ip, i64, d, d, d, ctypes.c_int, _dp, _lp]
         L.tpo_bh_frozen.restype = d
         L.tpo_bh_order.argtypes = [_dp, _ip, i64, ctypes.c_int, _lp]
@@ -220,6 +225,94 @@ def dense_fractional_matrix(V, F, sigma):
                 for j in verts:
                     L[i, j] += (phiS[i] - phiT[i]) * (phiS[j] - phiT[j]) * h
     return L
+
+
+# ----------------------------------------------------------------------------------
+# The inner-product operator A = B + B0 (Sec. 2.3; discrete terms in Sec. 3.3; applied in
+# the factored form of Sec. 5.1.2 and 5.1.3).  Its kernel exponent is 2s (sigma = s - 1).
+
+def face_gradients(V, F, u):
+    """D u(S): gradient of the piecewise linear u on every face (nF x k x 3)."""
+    V, F = _prep(V, F)
+    U = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(V.shape[0], -1))
+    k = U.shape[1]
+    Du = np.empty((F.shape[0], k, 3))
+    lib().tpo_face_gradients(_d(V), _i(F), F.shape[0], _d(U), k, _d(Du))
+    return Du
+
+
+def sobolev_apply(V, F, u, s=None, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
+    """A u = (B + B0) u for u of shape (nV,) or (nV, k), k <= 64."""
+    V, F = _prep(V, F)
+    if s is None:
+        s = sobolev_s(alpha, beta)
+    u = np.asarray(u, dtype=np.float64)
+    vec = u.ndim == 1
+    U = np.ascontiguousarray(u.reshape(u.shape[0], -1))
+    k = U.shape[1]
+    Au = np.empty_like(U)
+    rc = lib().tpo_sobolev_apply(_d(V), V.shape[0], _i(F), F.shape[0], s, _d(U), k, _d(Au))
+    if rc != 0:
+        raise ValueError("k must be in [1, 64]")
+    return Au[:, 0] if vec else Au
+
+
+def sobolev_at_vertices(V, F, u, verts, s):
+    """Exact (A u) at the listed vertices only (rows of the incident faces)."""
+    V, F = _prep(V, F)
+    U = np.ascontiguousarray(np.asarray(u, dtype=np.float64).reshape(V.shape[0], -1))
+    k = U.shape[1]
+    rows = _incident_faces(F, verts)
+    z = np.zeros((F.shape[0], 4 * k))
+    zr = np.empty((rows.size, 4 * k))
+    lib().tpo_sobolev_rowlist(_d(V), V.shape[0], _i(F), F.shape[0], s, _d(U), k,
+                              rows.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), rows.size, _d(zr))
+    z[rows] = zr
+    Au = np.empty((V.shape[0], k))
+    lib().tpo_sobolev_gather(_d(V), _i(F), F.shape[0], V.shape[0], _d(z), k, _d(Au))
+    return Au[np.asarray(verts)]
+
+
+def dense_sobolev_matrices(V, F, s):
+    """|V| x |V| matrices B and B0 assembled pair by pair from eqs. DiscreteHighOrderTerm and
+    DiscreteLowOrderTerm (tiny meshes only), over all ordered pairs S != T.
+
+    D phi_i(S) is taken from its definition d phi_i (df)^+ (Sec. 2.3): df is the 3 x 2
+    Jacobian of the affine map from the unit triangle onto S, and ^+ its Moore-Penrose
+    pseudoinverse (numpy.linalg.pinv).  K2(S,T) = |N_S . (X_S - X_T)|^2 / |X_S - X_T|^4 is
+    used as written, not symmetrized."""
+    V, F = _prep(V, F)
+    X, N, A = faces(V, F)
+    nV, nF = V.shape[0], F.shape[0]
+    # barycentric coordinates on the unit triangle: phi_0 = 1 - x - y, phi_1 = x, phi_2 = y
+    dphi_ref = np.array([[-1.0, -1.0], [1.0, 0.0], [0.0, 1.0]])
+    Dphi = []
+    for S in range(nF):
+        fi, fj, fk = V[F[S]]
+        df = np.stack([fj - fi, fk - fi], axis=1)      # 3 x 2
+        pinv = np.linalg.pinv(df)                       # 2 x 3
+        Dphi.append({int(F[S][c]): dphi_ref[c] @ pinv for c in range(3)})
+    B = np.zeros((nV, nV))
+    B0 = np.zeros((nV, nV))
+    zero = np.zeros(3)
+    for S in range(nF):
+        for T in range(nF):
+            if S == T:
+                continue
+            verts = sorted(set(F[S].tolist()) | set(F[T].tolist()))
+            d = X[S] - X[T]
+            r2 = float(d @ d)
+            h = r2 ** (-s) * A[S] * A[T]
+            K2 = float(N[S] @ d) ** 2 / r2 ** 2
+            for i in verts:
+                gi = Dphi[S].get(i, zero) - Dphi[T].get(i, zero)
+                pi = (1.0 / 3.0 if i in F[S] else 0.0) - (1.0 / 3.0 if i in F[T] else 0.0)
+                for j in verts:
+                    gj = Dphi[S].get(j, zero) - Dphi[T].get(j, zero)
+                    pj = (1.0 / 3.0 if j in F[S] else 0.0) - (1.0 / 3.0 if j in F[T] else 0.0)
+                    B[i, j] += float(gi @ gj) * h
+                    B0[i, j] += pi * pj * h * K2
+    return B, B0
 
 
 # ----------------------------------------------------------------------------------

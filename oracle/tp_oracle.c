@@ -347,6 +347,146 @@ EXPORT int tpo_fractional_apply(const double* V, int64_t nV, const int32_t* F, i
 }
 
 /* ------------------------------------------------------------------------- */
+/* The operator A = B + B0 of the inner product (Sec. 2.3, the high- and low-order terms;
+ * discretized in Sec. 3.3, eqs. DiscreteHighOrderTerm and DiscreteLowOrderTerm) applied to
+ * k columns, with sigma = s - 1 so that |d|^-(2 sigma + 2) = |d|^-2s:
+ *
+ *   (B u)_i  = sum_{S != T} < D phi_i(S) - D phi_i(T), D u(S) - D u(T) > |d|^-2s a_S a_T
+ *   (B0 u)_i = sum_{S != T} (phibar_i(S) - phibar_i(T)) (ubar(S) - ubar(T)) |d|^-2s K2(S,T) a_S a_T
+ *
+ * d = X_S - X_T; K2(S,T) = (N_S . d)^2 / |d|^4 is the discrete tangent-point kernel with
+ * exponents 2 and 4; D u(S) is the gradient of the piecewise linear u on S,
+ * D phi_i(S) = N_S x (f_k - f_j) / (2 a_S) for the corners (i, j, k) of S taken cyclically,
+ * i.e. c_S x (f_k - f_j) / |c_S|^2 with c_S = (f_j - f_i) x (f_k - f_i).  Renaming S <-> T in
+ * the parts that carry phi_i(T) (as for the fractional operator):
+ *
+ *   (B u)_i  = 2 sum_S < D phi_i(S), zB(S) >,  zB(S) = sum_{T != S} |d|^-2s a_S a_T (D u(S) - D u(T))
+ *   (B0 u)_i = 2 sum_S phibar_i(S) z0(S),
+ *              z0(S) = sum_{T != S} |d|^-2s (K2(S,T) + K2(T,S)) / 2 a_S a_T (ubar(S) - ubar(T)),
+ *
+ * where only the symmetric part of K2 survives because the rest of the summand is
+ * symmetric in (S, T).  zrow[(S - s0) 4k + 4c + m] = zB(S)[c][m] for m < 3, z0(S)[c] for m = 3. */
+static void face_gradients(const double* V, const int32_t* F, int64_t nF, const double* u, int k,
+                           double* Du /* nF x k x 3 */)
+{
+    for (int64_t S = 0; S < nF; ++S) {
+        double X[3], N[3], a, c[3];
+        face_quantities(V, F, S, X, N, &a, c);
+        double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        for (int cc = 0; cc < k; ++cc)
+            for (int m = 0; m < 3; ++m) Du[(S * k + cc) * 3 + m] = 0.0;
+        for (int corner = 0; corner < 3; ++corner) {
+            const double* fj = V + 3 * (int64_t)F[3 * S + (corner + 1) % 3];
+            const double* fk = V + 3 * (int64_t)F[3 * S + (corner + 2) % 3];
+            double e[3] = {fk[0] - fj[0], fk[1] - fj[1], fk[2] - fj[2]};
+            double g[3] = {(c[1] * e[2] - c[2] * e[1]) / c2, (c[2] * e[0] - c[0] * e[2]) / c2,
+                           (c[0] * e[1] - c[1] * e[0]) / c2};
+            int64_t i = F[3 * S + corner];
+            for (int cc = 0; cc < k; ++cc)
+                for (int m = 0; m < 3; ++m) Du[(S * k + cc) * 3 + m] += u[i * k + cc] * g[m];
+        }
+    }
+}
+
+EXPORT void tpo_face_gradients(const double* V, const int32_t* F, int64_t nF, const double* u, int k,
+                               double* Du)
+{
+    face_gradients(V, F, nF, u, k, Du);
+}
+
+static void sobolev_row(const double* X, const double* N, const double* A, const double* ub,
+                        const double* Du, int64_t nF, int k, double s, int64_t S, double* out)
+{
+    double accB[64 * 3], acc0[64];
+    for (int c = 0; c < 3 * k; ++c) accB[c] = 0.0;
+    for (int c = 0; c < k; ++c) acc0[c] = 0.0;
+    for (int64_t T = 0; T < nF; ++T) {
+        if (T == S) continue;
+        double d[3] = {X[3 * S] - X[3 * T], X[3 * S + 1] - X[3 * T + 1], X[3 * S + 2] - X[3 * T + 2]};
+        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        double h = pow(r2, -s) * A[S] * A[T];   /* |d|^-2s a_S a_T */
+        double qS = N[3 * S] * d[0] + N[3 * S + 1] * d[1] + N[3 * S + 2] * d[2];
+        double qT = N[3 * T] * d[0] + N[3 * T + 1] * d[1] + N[3 * T + 2] * d[2];
+        double k2 = 0.5 * (qS * qS / (r2 * r2) + qT * qT / (r2 * r2));
+        for (int c = 0; c < k; ++c) {
+            for (int m = 0; m < 3; ++m)
+                accB[3 * c + m] += (Du[(S * k + c) * 3 + m] - Du[(T * k + c) * 3 + m]) * h;
+            acc0[c] += (ub[S * k + c] - ub[T * k + c]) * h * k2;
+        }
+    }
+    for (int c = 0; c < k; ++c) {
+        for (int m = 0; m < 3; ++m) out[4 * c + m] = accB[3 * c + m];
+        out[4 * c + 3] = acc0[c];
+    }
+}
+
+static void sobolev_prepare(const double* V, const int32_t* F, int64_t nF, const double* u, int k,
+                            double** X, double** N, double** A, double** ub, double** Du)
+{
+    double* C = malloc(sizeof(double) * 3 * nF);
+    *X = malloc(sizeof(double) * 3 * nF);
+    *N = malloc(sizeof(double) * 3 * nF);
+    *A = malloc(sizeof(double) * nF);
+    *ub = malloc(sizeof(double) * nF * k);
+    *Du = malloc(sizeof(double) * nF * k * 3);
+    all_faces(V, F, nF, *X, *N, *A, C);
+    for (int64_t S = 0; S < nF; ++S)
+        for (int c = 0; c < k; ++c)
+            (*ub)[S * k + c] = (u[(int64_t)F[3 * S] * k + c] + u[(int64_t)F[3 * S + 1] * k + c] +
+                                u[(int64_t)F[3 * S + 2] * k + c]) / 3.0;
+    face_gradients(V, F, nF, u, k, *Du);
+    free(C);
+}
+
+EXPORT void tpo_sobolev_rowlist(const double* V, int64_t nV, const int32_t* F, int64_t nF, double s,
+                                const double* u, int k, const int64_t* rows, int64_t nrows, double* zrow)
+{
+    (void)nV;
+    double *X, *N, *A, *ub, *Du;
+    sobolev_prepare(V, F, nF, u, k, &X, &N, &A, &ub, &Du);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t q = 0; q < nrows; ++q) sobolev_row(X, N, A, ub, Du, nF, k, s, rows[q], zrow + q * 4 * k);
+    free(X); free(N); free(A); free(ub); free(Du);
+}
+
+/* (A u)_i = 2 sum_S (< D phi_i(S), zB(S) > + phibar_i(S) z0(S)) over the faces S with corner i. */
+EXPORT void tpo_sobolev_gather(const double* V, const int32_t* F, int64_t nF, int64_t nV, const double* z,
+                               int k, double* Au)
+{
+    memset(Au, 0, sizeof(double) * nV * k);
+    for (int64_t S = 0; S < nF; ++S) {
+        double X[3], N[3], a, c[3];
+        face_quantities(V, F, S, X, N, &a, c);
+        double c2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+        for (int corner = 0; corner < 3; ++corner) {
+            const double* fj = V + 3 * (int64_t)F[3 * S + (corner + 1) % 3];
+            const double* fk = V + 3 * (int64_t)F[3 * S + (corner + 2) % 3];
+            double e[3] = {fk[0] - fj[0], fk[1] - fj[1], fk[2] - fj[2]};
+            double g[3] = {(c[1] * e[2] - c[2] * e[1]) / c2, (c[2] * e[0] - c[0] * e[2]) / c2,
+                           (c[0] * e[1] - c[1] * e[0]) / c2};
+            int64_t i = F[3 * S + corner];
+            for (int cc = 0; cc < k; ++cc) {
+                const double* zc = z + S * 4 * k + 4 * cc;
+                Au[i * k + cc] += 2.0 * (g[0] * zc[0] + g[1] * zc[1] + g[2] * zc[2] + zc[3] / 3.0);
+            }
+        }
+    }
+}
+
+EXPORT int tpo_sobolev_apply(const double* V, int64_t nV, const int32_t* F, int64_t nF, double s,
+                             const double* u, int k, double* Au)
+{
+    if (k < 1 || k > 64) return 1;
+    double* z = malloc(sizeof(double) * nF * 4 * k);
+    int64_t* rows = malloc(sizeof(int64_t) * nF);
+    for (int64_t S = 0; S < nF; ++S) rows[S] = S;
+    tpo_sobolev_rowlist(V, nV, F, nF, s, u, k, rows, nF, z);
+    tpo_sobolev_gather(V, F, nF, nV, z, k, Au);
+    free(z); free(rows);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Barnes-Hut approximation of the energy (Sec. 4.1) and its differential (Sec. 4.2).
  *
  * Tree (reading: the paper names a BVH with at most 8 faces per leaf and leaves the

@@ -253,6 +253,90 @@ def test_fractional_scaling_and_rigid(noisy2):
     assert np.abs(O.fractional_apply(noisy2.V, noisy2.F, ones, sigma)).max() < 1e-12 * np.abs(L1).max()
 
 
+# ------------------------------------------------------- inner-product operator A = B + B0
+
+def _planar_grid(n=5):
+    xs, ys = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    V = np.stack([xs.ravel() * 0.3, ys.ravel() * 0.2, np.zeros(n * n)], 1) + [0.1, -0.4, 2.0]
+    V[:, :2] += 0.03 * np.random.default_rng(5).standard_normal((n * n, 2))
+    F = []
+    for i in range(n - 1):
+        for j in range(n - 1):
+            a, b, c, d = i * n + j, (i + 1) * n + j, (i + 1) * n + j + 1, i * n + j + 1
+            F += [[a, b, c], [a, c, d]]
+    return V, np.array(F, np.int32)
+
+
+def test_face_gradients_of_linear_functions(noisy2):
+    """D u of u(x) = <c, x> on a face is the part of c in the face's plane, (I - N N^T) c,
+    whatever the corner order or orientation of the face (the gradient of Sec. 2.3 read as
+    N x e_jk / (2 a) with unnormalized opposite edges)."""
+    c = np.array([[0.3, -1.2, 0.7], [2.0, 0.5, -0.1]]).T           # two linear functions
+    u = noisy2.V @ c
+    Du = O.face_gradients(noisy2.V, noisy2.F, u)
+    _, N, _ = O.faces(noisy2.V, noisy2.F)
+    for col in range(2):
+        want = c[:, col][None, :] - (N @ c[:, col])[:, None] * N
+        assert rel(Du[:, col, :], want) < 1e-13
+    F2 = noisy2.F[:, [1, 2, 0]]
+    F3 = noisy2.F[:, [0, 2, 1]]
+    assert rel(O.face_gradients(noisy2.V, F2, u), Du) < 1e-13
+    assert rel(O.face_gradients(noisy2.V, F3, u), Du) < 1e-13
+
+
+@pytest.mark.parametrize("s", [5.0 / 3.0, 1.25])
+def test_sobolev_matches_pairwise_assembly(tiny, s):
+    """The oracle's A u (factored, symmetrized low-order kernel) equals (B + B0) u with B and
+    B0 assembled pair by pair from eqs. DiscreteHighOrderTerm / DiscreteLowOrderTerm, D phi_i
+    from the pseudoinverse of df and K2 taken unsymmetrized."""
+    B, B0 = O.dense_sobolev_matrices(tiny.V, tiny.F, s)
+    u = RNG.standard_normal((tiny.nV, 3))
+    assert rel(O.sobolev_apply(tiny.V, tiny.F, u, s), (B + B0) @ u) < 1e-12
+    # each term is present: neither is negligible next to the other on this mesh
+    assert np.linalg.norm(B0 @ u) > 1e-3 * np.linalg.norm(B @ u)
+
+
+def test_sobolev_matrix_properties(tiny):
+    """B and B0 are symmetric, positive semidefinite and annihilate constants."""
+    B, B0 = O.dense_sobolev_matrices(tiny.V, tiny.F, 5.0 / 3.0)
+    for M in (B, B0):
+        scale = np.abs(M).max()
+        assert np.abs(M - M.T).max() < 1e-13 * scale
+        assert np.abs(M.sum(1)).max() < 1e-12 * scale
+        assert np.linalg.eigvalsh(M).min() > -1e-12 * scale
+
+
+def test_sobolev_planar_mesh():
+    """On a planar mesh N . d = 0 for every pair, so B0 = 0, and D u of a linear u is the
+    same on every face, so A u = 0; a quadratic u is not annihilated."""
+    V, F = _planar_grid()
+    s = 5.0 / 3.0
+    lin = V @ np.array([0.4, -0.9, 0.0]) + 0.25
+    quad = V[:, 0] ** 2 - 0.5 * V[:, 1] ** 2
+    A_quad = O.sobolev_apply(V, F, quad, s)
+    assert np.abs(O.sobolev_apply(V, F, lin, s)).max() < 1e-11 * np.abs(A_quad).max()
+    assert np.abs(A_quad).max() > 1e-3
+
+
+def test_sobolev_scaling_and_rigid(noisy2):
+    """B and B0 have the same units (the reason for K2 in Sec. 2.3): under f -> lambda f the
+    whole operator scales as lambda^(2 - 2s); rigid motions leave it unchanged."""
+    s = 5.0 / 3.0
+    u = RNG.standard_normal((noisy2.nV, 2))
+    A1 = O.sobolev_apply(noisy2.V, noisy2.F, u, s)
+    for lam in (0.6, 1.7):
+        A2 = O.sobolev_apply(lam * noisy2.V, noisy2.F, u, s)
+        assert rel(A2, lam ** (2 - 2 * s) * A1) < 1e-12
+    Q = random_rotation(RNG)
+    A3 = O.sobolev_apply(noisy2.V @ Q.T + 3.0, noisy2.F, u, s)
+    assert rel(A3, A1) < 1e-12
+    ones = np.ones((noisy2.nV, 1))
+    assert np.abs(O.sobolev_apply(noisy2.V, noisy2.F, ones, s)).max() < 1e-12 * np.abs(A1).max()
+    # sampled rows agree with the full apply
+    verts = [0, 7, noisy2.nV - 1]
+    assert rel(O.sobolev_at_vertices(noisy2.V, noisy2.F, u, verts, s), A1[verts]) < 1e-13
+
+
 # ----------------------------------------------------------- Laplacian and constraints
 
 def test_cotan_properties(noisy2):
