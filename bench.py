@@ -64,6 +64,42 @@ def frac_flop_per_pair(k: float) -> float:
     return 12.0 + 3.0 * k
 
 
+def sobolev_flop_per_pair(k: float) -> float:
+    # d 3, |d|^2 5, r2^-s a_T 4, the low-order weight w (q_S^2 + q_T^2) / r2^2 17 (two dot
+    # products, a reciprocal and five products / sums); per column 4 differences + 4 FMA
+    return 29.0 + 12.0 * k
+
+
+def sobolev_report(tp, P, u, launches: int = 10) -> dict:
+    """A u = (B + B0) u (the inner product's operator) with the three columns of u, timed
+    outside the step: the pair kernel by HIP events on its stream, the whole call by the
+    host clock around synchronized calls."""
+    import torch
+
+    Au = torch.empty_like(u)
+    for _ in range(2):
+        P.sobolev_apply(u, out=Au)
+    torch.cuda.synchronize()
+    tp.profile_reset()
+    tp.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(launches):
+        P.sobolev_apply(u, out=Au)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tp.profile_enable(False)
+    st = tp.profile_get(tp.KIND_SOBOLEV)
+    n = max(1, st["launches"])
+    ms = st["ms_total"] / n
+    k = st["cols_total"] / max(1.0, st["pairs_total"])
+    pairs = st["pairs_total"] / n
+    tflops = sobolev_flop_per_pair(k) * pairs / (ms * 1e-3) / 1e12
+    return {"avg_launch_ms": ms, "call_ms": 1e3 * wall / launches, "columns": k,
+            "flop_per_pair": sobolev_flop_per_pair(k), "achieved_tflops": tflops,
+            "frac": tflops / PEAK_FP32_VALU_TFLOPS, "pairs_per_s": pairs / (ms * 1e-3),
+            "launches": int(st["launches"])}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,6 +461,7 @@ def main():
     frac_ms = f["ms_total"] / max(1, f["launches"])
     frac_tflops = frac_flop_per_pair(kfrac) * (f["pairs_total"] / max(1, f["launches"])) / (frac_ms * 1e-3) / 1e12
     cg_ms = [float(np.mean([r.t_ms[0] for r in reps])), float(np.mean([r.t_ms[2] for r in reps]))]
+    sob = sobolev_report(tp, P, u)
 
     out = {
         "metric": "tri-pair interactions/s (E+dE, H-apply) vs FP32 roofline; served steps/s + p99",
@@ -476,6 +513,7 @@ def main():
                 "achieved_tflops": frac_tflops, "frac": frac_tflops / PEAK_FP32_VALU_TFLOPS,
                 "pairs_per_s": (f["pairs_total"] / max(1, f["launches"])) / (frac_ms * 1e-3),
             },
+            "sobolev_apply": sob,
             "cg_ms": {"solve1": cg_ms[0], "solve2": cg_ms[1]},
             "cg_iters": [int(reps[-1].cg_iters[0]), int(reps[-1].cg_iters[1])],
             "pcg": pcg_report(mesh.nV, 3, cg_ms, [int(reps[-1].cg_iters[0]), int(reps[-1].cg_iters[1])]),

@@ -119,6 +119,24 @@ TP_API tp_status tp_fractional_apply(const double* V, int64_t nV, const int32_t*
                               const tp_params* params, const double* u, int k,
                               double* Lu_out, void* stream);
 
+/* Au = A u = (B + B0) u for k columns: the operator of the paper's inner product (Sec. 2.3,
+ * high- and low-order terms; discrete forms eqs. DiscreteHighOrderTerm and
+ * DiscreteLowOrderTerm of Sec. 3.3), applied in the factored form of Sec. 5.1.2 / 5.1.3:
+ *   B u  = 2 (diag(a) D)^T [diag(diag(a)^-1 H a) - H] diag(a) D u,  H_ST = (1 - delta_ST)|X_S - X_T|^-2s,
+ *   B0 u = 2 U^T [diag(diag(a)^-1 H0 a) - H0] U u,  H0_ST = H_ST (K2(S,T) + K2(T,S)) / 2,
+ * with s = (beta - 2) / alpha (sigma = s - 1 in the paper's notation for these terms),
+ * K2(S,T) = (N_S . (X_S - X_T))^2 / |X_S - X_T|^4, D u(S) the gradient of the piecewise
+ * linear u on face S (N_S x opposite edge / (2 a_S) per corner) and U the face average times
+ * the area.  A annihilates constants; it is symmetric positive semidefinite.  Each column is
+ * one scalar function; the operator A_3 of the descent direction applies A to the three
+ * coordinate columns.  u, Au_out: device, nV x k row-major double, 1 <= k <= 64; the caller
+ * owns both.  The pair terms follow params->precision (FP64, or FP32 with FP64 sums; the
+ * near-field FP64 option of the energy applies FP32 hi/lo here).  Errors: TP_E_INVALID_ARGUMENT
+ * for NULL pointers or k outside [1, 64], and the mesh checks of tp_problem_create. */
+TP_API tp_status tp_sobolev_apply(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                                  const tp_params* params, const double* u, int k,
+                                  double* Au_out, void* stream);
+
 /* Report of one preconditioner application (two CG solves). */
 typedef struct {
     int    cg_iters[2];      /* largest iteration count over the columns, per solve      */
@@ -154,6 +172,7 @@ TP_API tp_status tp_problem_get_vertices(tp_problem* prob, double* V_out);
 TP_API tp_status tp_problem_energy(tp_problem* prob, double* E_out);
 TP_API tp_status tp_problem_gradient(tp_problem* prob, double* E_out, double* dE_out);
 TP_API tp_status tp_problem_fractional_apply(tp_problem* prob, const double* u, int k, double* Lu_out);
+TP_API tp_status tp_problem_sobolev_apply(tp_problem* prob, const double* u, int k, double* Au_out);
 TP_API tp_status tp_problem_precond_apply(tp_problem* prob, const double* b, int k, double* x_out,
                                    tp_solve_report* report);
 
@@ -254,11 +273,12 @@ TP_API const char* tp_last_error(void);
 /* Kernel timing for roofline reports.  When enabled, every all-pairs kernel launch is
  * bracketed by HIP events recorded on the stream it runs on; the elapsed device time,
  * the number of ordered face pairs it covered and the launch count are accumulated per
- * kind: 0 = energy, 1 = energy + differential, 2 = fractional apply.  Process-global. */
+ * kind: 0 = energy, 1 = energy + differential, 2 = fractional apply, 3 = the inner-product
+ * operator A (tp_sobolev_apply; the pair kernel alone).  Process-global. */
 typedef struct {
     double  ms_total;      /* summed device time of the launches                        */
     double  pairs_total;   /* summed ordered pairs S != T evaluated (columns not counted) */
-    double  cols_total;    /* summed pairs x columns (fractional apply only)             */
+    double  cols_total;    /* summed pairs x columns (fractional apply and operator A)   */
     int64_t launches;
 } tp_kernel_stats;
 

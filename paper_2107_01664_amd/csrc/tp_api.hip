@@ -1,6 +1,7 @@
 // C-ABI of libtpsurf: validation, resident problem state and the host orchestration of
 // the hot path (energy, differential, fractional apply, preconditioner, descent step).
 #include "tp_solver.h"
+#include "tp_sobolev.h"
 
 #include <algorithm>
 #include <cmath>
@@ -52,8 +53,9 @@ const DeviceInfo& device_info()
 struct Profiler {
     std::mutex mu;
     bool on = false;
-    tp_kernel_stats st[3];
+    tp_kernel_stats st[4];
 };
+constexpr int kKindSobolev = 3;   // profile slot of the inner-product operator's pair kernel
 static Profiler g_prof;
 
 struct PairTimer {
@@ -1289,6 +1291,41 @@ tp_status run_fractional(tp_problem* P, const double* u, int ldu, int k, double*
     return enqueue_fractional(B, &u, ldu, k, &Lu, ldl);
 }
 
+// Au = (B + B0) u for columns of u (row stride ldu) into Au (row stride ldo), in groups of
+// kSobCols columns (one pair launch per group).
+tp_status run_sobolev(tp_problem* P, const double* u, int ldu, int k, double* Au, int ldo)
+{
+    hipStream_t s = P->stream;
+    const int prec = P->prm.precision;
+    TP_TRY(ensure_vf(P));
+    // order of the operator: 2s with s = (beta - 2) / alpha, the order of the energy's differential
+    const double sexp = (P->prm.beta - 2.0) / P->prm.alpha;
+    for (int c0 = 0; c0 < k; c0 += kSobCols) {
+        const int kc = std::min(kSobCols, k - c0);
+        SobolevCall c;
+        c.fd = &P->fd;
+        c.plan = sobolev_plan(prec, kc, P->nF, P->cap);
+        c.precision = prec;
+        c.s = sexp;
+        c.V = P->V.p;
+        c.F = P->F.p;
+        c.nV = P->nV;
+        c.nF = P->nF;
+        c.vf_off = P->vf_off.p;
+        c.vf_idx = P->vf_idx.p;
+        TP_TRY(P->ub.ensure(sobolev_face_bytes(prec, kc, P->cap), s));
+        TP_TRY(P->part.ensure((size_t)c.plan.n_split * 4 * kc * c.plan.irows, s));
+        TP_TRY(P->zbuf.ensure((size_t)4 * kc * c.plan.irows, s));
+        c.fu = P->ub.p;
+        c.part = P->part.p;
+        c.z = P->zbuf.p;
+        const double pairs = (double)P->nF * (double)(P->nF - 1);
+        PairTimer t(kKindSobolev, pairs, pairs * kc, s);
+        TP_HIP(launch_sobolev(c, u, ldu, kc, Au, ldo, c0, t.on ? t.a : nullptr, t.on ? t.b : nullptr, s));
+    }
+    return TP_OK;
+}
+
 // x = C^+ b for k columns (row stride k); b is overwritten with its projection.
 tp_status run_cg(tp_problem* P, double* b, double* x, int k, int* it_max, double* res_max)
 {
@@ -1969,6 +2006,18 @@ tp_status tp_problem_fractional_apply(tp_problem* P, const double* u, int k, dou
     return TP_OK;
 }
 
+tp_status tp_problem_sobolev_apply(tp_problem* P, const double* u, int k, double* Au_out)
+{
+    TP_TRY(bind(P));
+    if (!u || !Au_out) return fail(TP_E_INVALID_ARGUMENT, "u and Au_out must be non-NULL");
+    if (k < 1 || k > kMaxCols) return fail(TP_E_INVALID_ARGUMENT, "k must lie in [1, 64]");
+    set_error("");
+    TP_TRY(ensure_geometry(P));
+    TP_TRY(run_sobolev(P, u, k, k, Au_out, k));
+    TP_HIP(hipStreamSynchronize(P->stream));
+    return TP_OK;
+}
+
 tp_status tp_problem_precond_apply(tp_problem* P, const double* b, int k, double* x_out,
                                    tp_solve_report* report)
 {
@@ -2047,6 +2096,16 @@ tp_status tp_fractional_apply(const double* V, int64_t nV, const int32_t* F, int
     ProblemGuard g;
     TP_TRY(tp_problem_create(V, nV, F, nF, params, stream, &g.p));
     return tp_problem_fractional_apply(g.p, u, k, Lu_out);
+}
+
+tp_status tp_sobolev_apply(const double* V, int64_t nV, const int32_t* F, int64_t nF,
+                           const tp_params* params, const double* u, int k, double* Au_out,
+                           void* stream)
+{
+    if (k < 1 || k > kMaxCols) return fail(TP_E_INVALID_ARGUMENT, "k must lie in [1, 64]");
+    ProblemGuard g;
+    TP_TRY(tp_problem_create(V, nV, F, nF, params, stream, &g.p));
+    return tp_problem_sobolev_apply(g.p, u, k, Au_out);
 }
 
 tp_status tp_precond_apply(const double* V, int64_t nV, const int32_t* F, int64_t nF,
@@ -2134,7 +2193,7 @@ tp_status tp_profile_reset(void)
 
 tp_status tp_profile_get(int kind, tp_kernel_stats* out)
 {
-    if (kind < 0 || kind > 2 || !out) return TP_E_INVALID_ARGUMENT;
+    if (kind < 0 || kind > 3 || !out) return TP_E_INVALID_ARGUMENT;
     std::lock_guard<std::mutex> lk(g_prof.mu);
     *out = g_prof.st[kind];
     return TP_OK;

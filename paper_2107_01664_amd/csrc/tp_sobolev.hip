@@ -1,0 +1,400 @@
+// The inner-product operator A = B + B0 (Sec. 2.3; discrete terms in Sec. 3.3, eqs.
+// DiscreteHighOrderTerm and DiscreteLowOrderTerm), applied in the factored form of
+// Sec. 5.1.2 and 5.1.3:
+//
+//   A u = 2 (diag(a) D)^T [diag(diag(a)^-1 H a) - H] (diag(a) D) u
+//       + 2 U^T [diag(diag(a)^-1 H0 a) - H0] U u,
+//
+// H_ST = |X_S - X_T|^-2s (sigma = s - 1), H0_ST = H_ST (K2(S,T) + K2(T,S)) / 2 with
+// K2(S,T) = (N_S . d)^2 / |d|^4 (the tangent-point kernel with exponents 2 and 4), D u(S)
+// the gradient of the piecewise linear u on face S, U the face average times the area.
+// Row S of a bracket applied to diag(a) v is sum_{T != S} H_ST a_T (v(S) - v(T)).
+//
+// Three passes per group of kc <= kSobCols columns:
+//   k_sob_face    per face and column: D u (3 values) and ubar, from V and F in FP64, stored
+//                 as one FP32 (or FP64) 4-vector per column, [cap][kc];
+//   k_sob32/64    the pair sums with the tiling of the other all-pairs kernels: an i-tile of
+//                 kBlock * NI faces in registers, j-tiles of kTileJ faces through LDS (every
+//                 lane reads the same face T), an (i-tiles) x (j-splits) grid whose partial
+//                 sums per split are added in order by launch_reduce_splits.  Per pair: d
+//                 (hi/lo), r2, w = r2^-s a_T by log2/exp2, q_S = N_S . d, q_T = N_T . d,
+//                 w0 = w (q_S^2 + q_T^2) / r2^2; zB += w (D u(S) - D u(T)), z0 += w0 (ubar(S) - ubar(T));
+//   k_sob_gather  (A u)_i = sum over the faces S around i of 2 a_S (<D phi_i(S), zB(S)> + z0(S) / 6)
+//                 (the 1/2 of the symmetrized K2 and phibar = 1/3 give the 1/6), with
+//                 D phi_i(S) = c_S x (f_k - f_j) / |c_S|^2 in FP64 for the corners i, j, k of
+//                 S in cyclic order, c_S = (f_j - f_i) x (f_k - f_i).
+//
+// The diagonal S = T contributes nothing: d = 0 there, so both differences and q vanish;
+// r2 is set to 1 on it to keep the powers finite.
+#include "tp_sobolev.h"
+
+#include <algorithm>
+#include <mutex>
+#include <unordered_map>
+
+namespace tp {
+
+namespace {
+
+inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+constexpr int kNiSob32 = 2;
+
+struct SobArgs {
+    const void* fx;     // float4 (Xhi, a) or double4 (X, a)
+    const void* fl;     // float4 (Xlo, 0)
+    const void* fn;     // float4 or double4 (N, 0)
+    const void* fu;     // [cap][KC] 4-vectors (D u, ubar)
+    double* part;       // [n_split][4 KC][irows]
+    int64_t irows;
+    int n_itiles, tiles_per_split, ntiles_j;
+};
+
+__device__ __forceinline__ bool hits_diag(int64_t j0, int64_t ibase, int ispan)
+{
+    return j0 < ibase + ispan && j0 + kTileJ > ibase;
+}
+
+// ------------------------------------------------------------------ per-face columns
+
+template <class R, class R4>
+__global__ void k_sob_face(const double* __restrict__ V, const int32_t* __restrict__ F, int64_t nF,
+                           int64_t cap, const double* __restrict__ u, int ldu, int kc, R4* __restrict__ fu)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cap) return;
+    if (t >= nF) {
+        for (int c = 0; c < kc; ++c) fu[t * kc + c] = R4{0, 0, 0, 0};
+        return;
+    }
+    int32_t id[3];
+    double p[3][3];
+    for (int m = 0; m < 3; ++m) {
+        id[m] = F[3 * t + m];
+        for (int x = 0; x < 3; ++x) p[m][x] = V[3 * (int64_t)id[m] + x];
+    }
+    const double e1[3] = {p[1][0] - p[0][0], p[1][1] - p[0][1], p[1][2] - p[0][2]};
+    const double e2[3] = {p[2][0] - p[0][0], p[2][1] - p[0][1], p[2][2] - p[0][2]};
+    const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                          e1[0] * e2[1] - e1[1] * e2[0]};
+    const double ic2 = 1.0 / (cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+    double g[3][3];   // D phi of each corner
+    for (int m = 0; m < 3; ++m) {
+        const double* pj = p[(m + 1) % 3];
+        const double* pk = p[(m + 2) % 3];
+        const double e[3] = {pk[0] - pj[0], pk[1] - pj[1], pk[2] - pj[2]};
+        g[m][0] = (cr[1] * e[2] - cr[2] * e[1]) * ic2;
+        g[m][1] = (cr[2] * e[0] - cr[0] * e[2]) * ic2;
+        g[m][2] = (cr[0] * e[1] - cr[1] * e[0]) * ic2;
+    }
+    for (int c = 0; c < kc; ++c) {
+        const double u0 = u[(int64_t)id[0] * ldu + c], u1 = u[(int64_t)id[1] * ldu + c],
+                     u2 = u[(int64_t)id[2] * ldu + c];
+        R4 o;
+        o.x = (R)(u0 * g[0][0] + u1 * g[1][0] + u2 * g[2][0]);
+        o.y = (R)(u0 * g[0][1] + u1 * g[1][1] + u2 * g[2][1]);
+        o.z = (R)(u0 * g[0][2] + u1 * g[1][2] + u2 * g[2][2]);
+        o.w = (R)((u0 + u1 + u2) / 3.0);
+        fu[t * kc + c] = o;
+    }
+}
+
+// ------------------------------------------------------------------ FP32 pair sums
+
+template <bool DIAG, int NI, int KC, bool HILO>
+__device__ __forceinline__ void sob_tile32(const float4* s_x, const float4* s_l, const float4* s_n,
+                                           const float4* s_u, int64_t j0, const float3 (&Sh)[NI],
+                                           const float3 (&Sl)[NI], const float3 (&Sn)[NI],
+                                           const float4 (&Su)[NI][KC], const int64_t (&Si)[NI], float ms,
+                                           float (&c)[NI][4 * KC])
+{
+    for (int jj = 0; jj < kTileJ; ++jj) {
+        const float4 tx = s_x[jj];
+        const float4 tn = s_n[jj];
+        const float4 tl = HILO ? s_l[jj] : make_float4(0.f, 0.f, 0.f, 0.f);
+        float4 tu[KC];
+#pragma unroll
+        for (int cc = 0; cc < KC; ++cc) tu[cc] = s_u[jj * KC + cc];
+#pragma unroll
+        for (int r = 0; r < NI; ++r) {
+            float dx, dy, dz;
+            if (HILO) {
+                dx = (Sh[r].x - tx.x) + (Sl[r].x - tl.x);
+                dy = (Sh[r].y - tx.y) + (Sl[r].y - tl.y);
+                dz = (Sh[r].z - tx.z) + (Sl[r].z - tl.z);
+            } else {
+                dx = Sh[r].x - tx.x;
+                dy = Sh[r].y - tx.y;
+                dz = Sh[r].z - tx.z;
+            }
+            float r2 = dx * dx + dy * dy + dz * dz;
+            if (DIAG) r2 = (Si[r] == j0 + jj) ? 1.0f : r2;
+            const float w = __builtin_amdgcn_exp2f(ms * __builtin_amdgcn_logf(r2)) * tx.w;
+            const float qs = Sn[r].x * dx + Sn[r].y * dy + Sn[r].z * dz;
+            const float qt = tn.x * dx + tn.y * dy + tn.z * dz;
+            const float inv = __builtin_amdgcn_rcpf(r2);
+            const float w0 = w * ((qs * qs + qt * qt) * (inv * inv));
+#pragma unroll
+            for (int cc = 0; cc < KC; ++cc) {
+                c[r][4 * cc + 0] += w * (Su[r][cc].x - tu[cc].x);
+                c[r][4 * cc + 1] += w * (Su[r][cc].y - tu[cc].y);
+                c[r][4 * cc + 2] += w * (Su[r][cc].z - tu[cc].z);
+                c[r][4 * cc + 3] += w0 * (Su[r][cc].w - tu[cc].w);
+            }
+        }
+    }
+}
+
+template <int NI, int KC, bool HILO>
+__global__ __launch_bounds__(kBlock) void k_sob32(SobArgs A, float ms)
+{
+    const int bi = (int)blockIdx.x % A.n_itiles;
+    const int bs = (int)blockIdx.x / A.n_itiles;
+    const float4* __restrict__ fx = static_cast<const float4*>(A.fx);
+    const float4* __restrict__ fl = static_cast<const float4*>(A.fl);
+    const float4* __restrict__ fn = static_cast<const float4*>(A.fn);
+    const float4* __restrict__ fu = static_cast<const float4*>(A.fu);
+    __shared__ float4 s_x[kTileJ], s_l[HILO ? kTileJ : 1], s_n[kTileJ], s_u[kTileJ * KC];
+    const int64_t ibase = (int64_t)bi * (kBlock * NI);
+    const int jt0 = bs * A.tiles_per_split;
+    const int jt1 = min(jt0 + A.tiles_per_split, A.ntiles_j);
+    float3 Sh[NI], Sl[NI], Sn[NI];
+    float4 Su[NI][KC];
+    int64_t Si[NI];
+    double acc[NI][4 * KC];
+#pragma unroll
+    for (int r = 0; r < NI; ++r) {
+        Si[r] = ibase + r * kBlock + threadIdx.x;
+        const float4 x = fx[Si[r]], n = fn[Si[r]];
+        Sh[r] = make_float3(x.x, x.y, x.z);
+        Sn[r] = make_float3(n.x, n.y, n.z);
+        if (HILO) {
+            const float4 l = fl[Si[r]];
+            Sl[r] = make_float3(l.x, l.y, l.z);
+        } else {
+            Sl[r] = make_float3(0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int cc = 0; cc < KC; ++cc) Su[r][cc] = fu[Si[r] * KC + cc];
+#pragma unroll
+        for (int q = 0; q < 4 * KC; ++q) acc[r][q] = 0.0;
+    }
+    for (int jt = jt0; jt < jt1; ++jt) {
+        const int64_t j0 = (int64_t)jt * kTileJ;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kTileJ; e += kBlock) {
+            s_x[e] = fx[j0 + e];
+            s_n[e] = fn[j0 + e];
+            if (HILO) s_l[e] = fl[j0 + e];
+        }
+        for (int e = threadIdx.x; e < kTileJ * KC; e += kBlock) s_u[e] = fu[j0 * KC + e];
+        __syncthreads();
+        float c[NI][4 * KC];
+#pragma unroll
+        for (int r = 0; r < NI; ++r)
+#pragma unroll
+            for (int q = 0; q < 4 * KC; ++q) c[r][q] = 0.f;
+        if (hits_diag(j0, ibase, kBlock * NI))
+            sob_tile32<true, NI, KC, HILO>(s_x, s_l, s_n, s_u, j0, Sh, Sl, Sn, Su, Si, ms, c);
+        else
+            sob_tile32<false, NI, KC, HILO>(s_x, s_l, s_n, s_u, j0, Sh, Sl, Sn, Su, Si, ms, c);
+#pragma unroll
+        for (int r = 0; r < NI; ++r)
+#pragma unroll
+            for (int q = 0; q < 4 * KC; ++q) acc[r][q] += (double)c[r][q];
+    }
+#pragma unroll
+    for (int r = 0; r < NI; ++r)
+#pragma unroll
+        for (int q = 0; q < 4 * KC; ++q) A.part[((int64_t)bs * 4 * KC + q) * A.irows + Si[r]] = acc[r][q];
+}
+
+// ------------------------------------------------------------------ FP64 pair sums
+
+template <int KC>
+__global__ __launch_bounds__(kBlock) void k_sob64(SobArgs A, double ms)
+{
+    const int bi = (int)blockIdx.x % A.n_itiles;
+    const int bs = (int)blockIdx.x / A.n_itiles;
+    const double4* __restrict__ dx4 = static_cast<const double4*>(A.fx);
+    const double4* __restrict__ dn4 = static_cast<const double4*>(A.fn);
+    const double4* __restrict__ fu = static_cast<const double4*>(A.fu);
+    __shared__ double4 s_x[kTileJ], s_n[kTileJ], s_u[kTileJ * KC];
+    const int64_t ibase = (int64_t)bi * kBlock;
+    const int jt0 = bs * A.tiles_per_split;
+    const int jt1 = min(jt0 + A.tiles_per_split, A.ntiles_j);
+    const int64_t Si = ibase + threadIdx.x;
+    const double4 x = dx4[Si], n = dn4[Si];
+    double4 Su[KC];
+    double acc[4 * KC];
+#pragma unroll
+    for (int cc = 0; cc < KC; ++cc) Su[cc] = fu[Si * KC + cc];
+#pragma unroll
+    for (int q = 0; q < 4 * KC; ++q) acc[q] = 0.0;
+    for (int jt = jt0; jt < jt1; ++jt) {
+        const int64_t j0 = (int64_t)jt * kTileJ;
+        __syncthreads();
+        for (int e = threadIdx.x; e < kTileJ; e += kBlock) {
+            s_x[e] = dx4[j0 + e];
+            s_n[e] = dn4[j0 + e];
+        }
+        for (int e = threadIdx.x; e < kTileJ * KC; e += kBlock) s_u[e] = fu[j0 * KC + e];
+        __syncthreads();
+        const bool diag = hits_diag(j0, ibase, kBlock);
+        for (int jj = 0; jj < kTileJ; ++jj) {
+            if (diag && Si == j0 + jj) continue;
+            const double4 t = s_x[jj], tn = s_n[jj];
+            const double dx = x.x - t.x, dy = x.y - t.y, dz = x.z - t.z;
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            const double w = pow(r2, ms) * t.w;
+            const double qs = n.x * dx + n.y * dy + n.z * dz;
+            const double qt = tn.x * dx + tn.y * dy + tn.z * dz;
+            const double w0 = w * (qs * qs + qt * qt) / (r2 * r2);
+#pragma unroll
+            for (int cc = 0; cc < KC; ++cc) {
+                const double4 tu = s_u[jj * KC + cc];
+                acc[4 * cc + 0] += w * (Su[cc].x - tu.x);
+                acc[4 * cc + 1] += w * (Su[cc].y - tu.y);
+                acc[4 * cc + 2] += w * (Su[cc].z - tu.z);
+                acc[4 * cc + 3] += w0 * (Su[cc].w - tu.w);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4 * KC; ++q) A.part[((int64_t)bs * 4 * KC + q) * A.irows + Si] = acc[q];
+}
+
+// ------------------------------------------------------------------ gather to vertices
+
+__global__ void k_sob_gather(int64_t nV, const int32_t* __restrict__ vf_off, const int32_t* __restrict__ vf_idx,
+                             const double* __restrict__ V, const int32_t* __restrict__ F,
+                             const double4* __restrict__ dxa, const double* __restrict__ z, int64_t zs, int kc,
+                             int ldo, int c0, double* __restrict__ Au)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nV * kc) return;
+    const int64_t v = t / kc;
+    const int c = (int)(t - v * kc);
+    double acc = 0.0;
+    for (int32_t q = vf_off[v]; q < vf_off[v + 1]; ++q) {
+        const int64_t f = vf_idx[q] / 3;
+        const int m = vf_idx[q] - 3 * (int)f;
+        const double* pi = V + 3 * (int64_t)F[3 * f + m];
+        const double* pj = V + 3 * (int64_t)F[3 * f + (m + 1) % 3];
+        const double* pk = V + 3 * (int64_t)F[3 * f + (m + 2) % 3];
+        const double e1[3] = {pj[0] - pi[0], pj[1] - pi[1], pj[2] - pi[2]};
+        const double e2[3] = {pk[0] - pi[0], pk[1] - pi[1], pk[2] - pi[2]};
+        const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                              e1[0] * e2[1] - e1[1] * e2[0]};
+        const double ic2 = 1.0 / (cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]);
+        const double e[3] = {pk[0] - pj[0], pk[1] - pj[1], pk[2] - pj[2]};
+        const double g0 = (cr[1] * e[2] - cr[2] * e[1]) * ic2;
+        const double g1 = (cr[2] * e[0] - cr[0] * e[2]) * ic2;
+        const double g2 = (cr[0] * e[1] - cr[1] * e[0]) * ic2;
+        const double* zc = z + (int64_t)(4 * c) * zs + f;
+        acc += 2.0 * dxa[f].w * (g0 * zc[0] + g1 * zc[zs] + g2 * zc[2 * zs] + zc[3 * zs] / 6.0);
+    }
+    Au[v * ldo + c0 + c] = acc;
+}
+
+// ------------------------------------------------------------------ dispatch
+
+const void* sob_fn(int precision, int kc)
+{
+    const bool hilo = precision == TP_PREC_FP32_HILO || precision == TP_PREC_FP32_NEAR64;
+    if (precision == TP_PREC_FP64) {
+        switch (kc) {
+        case 1: return (const void*)k_sob64<1>;
+        case 2: return (const void*)k_sob64<2>;
+        default: return (const void*)k_sob64<3>;
+        }
+    }
+    switch (kc) {
+    case 1: return hilo ? (const void*)k_sob32<kNiSob32, 1, true> : (const void*)k_sob32<kNiSob32, 1, false>;
+    case 2: return hilo ? (const void*)k_sob32<kNiSob32, 2, true> : (const void*)k_sob32<kNiSob32, 2, false>;
+    default: return hilo ? (const void*)k_sob32<kNiSob32, 3, true> : (const void*)k_sob32<kNiSob32, 3, false>;
+    }
+}
+
+int sob_occupancy(const void* fn)
+{
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> cache;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(fn);
+    if (it != cache.end()) return it->second;
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlock, 0) != hipSuccess || nb < 1) nb = 1;
+    cache[fn] = nb;
+    return nb;
+}
+
+template <int KC>
+void launch_pair_k(int precision, dim3 grid, const SobArgs& A, double sexp, hipStream_t st)
+{
+    const dim3 block(kBlock);
+    if (precision == TP_PREC_FP64)
+        hipLaunchKernelGGL(k_sob64<KC>, grid, block, 0, st, A, -sexp);
+    else if (precision == TP_PREC_FP32_HILO || precision == TP_PREC_FP32_NEAR64)
+        hipLaunchKernelGGL((k_sob32<kNiSob32, KC, true>), grid, block, 0, st, A, (float)-sexp);
+    else
+        hipLaunchKernelGGL((k_sob32<kNiSob32, KC, false>), grid, block, 0, st, A, (float)-sexp);
+}
+
+}  // namespace
+
+PairPlan sobolev_plan(int precision, int kc, int64_t nF, int64_t cap)
+{
+    kc = std::max(1, std::min(kc, kSobCols));
+    const int ni = precision == TP_PREC_FP64 ? 1 : kNiSob32;
+    return plan_pairs(nF, cap, ni, sob_occupancy(sob_fn(precision, kc)));
+}
+
+size_t sobolev_face_bytes(int precision, int kc, int64_t cap)
+{
+    return (size_t)cap * (size_t)kc * (precision == TP_PREC_FP64 ? sizeof(double4) : sizeof(float4));
+}
+
+hipError_t launch_sobolev(const SobolevCall& c, const double* u, int ldu, int kc, double* Au, int ldo,
+                          int c0, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
+{
+    if (kc < 1 || kc > kSobCols || !c.fd) return hipErrorInvalidValue;
+    const FaceData& fd = *c.fd;
+    const PairPlan& pl = c.plan;
+    // the kernels read faces [0, irows) and j-tiles [0, ntiles_j * kTileJ) of arrays of cap entries
+    if (pl.irows > fd.cap || (int64_t)pl.ntiles_j * kTileJ > fd.cap) return hipErrorInvalidValue;
+    const bool f64 = c.precision == TP_PREC_FP64;
+    if (f64)
+        hipLaunchKernelGGL((k_sob_face<double, double4>), dim3(nblk(fd.cap)), dim3(256), 0, s, c.V, c.F, c.nF,
+                           fd.cap, u + c0, ldu, kc, static_cast<double4*>(c.fu));
+    else
+        hipLaunchKernelGGL((k_sob_face<float, float4>), dim3(nblk(fd.cap)), dim3(256), 0, s, c.V, c.F, c.nF,
+                           fd.cap, u + c0, ldu, kc, static_cast<float4*>(c.fu));
+    SobArgs A;
+    A.fx = f64 ? (const void*)fd.dx : (const void*)fd.fx;
+    A.fl = fd.fl;
+    A.fn = f64 ? (const void*)fd.dn : (const void*)fd.fn;
+    A.fu = c.fu;
+    A.part = c.part;
+    A.irows = pl.irows;
+    A.n_itiles = pl.n_itiles;
+    A.tiles_per_split = pl.tiles_per_split;
+    A.ntiles_j = pl.ntiles_j;
+    const dim3 grid((unsigned)(pl.n_itiles * pl.n_split));
+    if (ev0) (void)hipEventRecord(ev0, s);
+    switch (kc) {
+    case 1: launch_pair_k<1>(c.precision, grid, A, c.s, s); break;
+    case 2: launch_pair_k<2>(c.precision, grid, A, c.s, s); break;
+    default: launch_pair_k<3>(c.precision, grid, A, c.s, s); break;
+    }
+    if (ev1) (void)hipEventRecord(ev1, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_reduce_splits(c.part, pl.n_split, 4 * kc, pl.irows, c.nF, c.z, pl.irows, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sob_gather, dim3(nblk(c.nV * kc)), dim3(256), 0, s, c.nV, c.vf_off, c.vf_idx, c.V, c.F,
+                       fd.dx, c.z, pl.irows, kc, ldo, c0, Au);
+    return hipGetLastError();
+}
+
+}  // namespace tp

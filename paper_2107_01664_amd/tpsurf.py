@@ -26,14 +26,15 @@ STATUS_NAMES = {
     7: "TP_E_SINGULAR_CONSTRAINTS", 8: "TP_E_DEVICE",
 }
 PREC_FP32_HILO, PREC_FP32, PREC_FP64, PREC_FP32_NEAR64 = 0, 1, 2, 3
-KIND_ENERGY, KIND_GRAD, KIND_FRAC = 0, 1, 2
+KIND_ENERGY, KIND_GRAD, KIND_FRAC, KIND_SOBOLEV = 0, 1, 2, 3
 
 # Every symbol the C-ABI exports (the header declares exactly these).
 EXPORTED = [
     "tp_params_default", "tp_energy", "tp_gradient", "tp_energy_faces", "tp_fractional_apply",
     "tp_precond_apply", "tp_problem_create", "tp_problem_destroy", "tp_problem_set_vertices",
     "tp_problem_get_vertices", "tp_problem_energy", "tp_problem_gradient",
-    "tp_problem_fractional_apply", "tp_problem_precond_apply", "tp_step_opts_default",
+    "tp_problem_fractional_apply", "tp_sobolev_apply", "tp_problem_sobolev_apply",
+    "tp_problem_precond_apply", "tp_step_opts_default",
     "tp_precond_step", "tp_last_error", "tp_profile_enable", "tp_profile_reset", "tp_profile_get",
     "tp_problem_poisson_solve", "tp_batch_step", "tp_problem_device_bytes",
     "tp_estimate_device_bytes", "tp_problem_bh_stats",
@@ -111,6 +112,8 @@ def lib() -> ctypes.CDLL:
         "tp_problem_energy": [vp, P(d)],
         "tp_problem_gradient": [vp, P(d), vp],
         "tp_problem_fractional_apply": [vp, vp, i32, vp],
+        "tp_sobolev_apply": [vp, i64, vp, i64, P(Params), vp, i32, vp, vp],
+        "tp_problem_sobolev_apply": [vp, vp, i32, vp],
         "tp_problem_precond_apply": [vp, vp, i32, vp, P(SolveReport)],
         "tp_problem_poisson_solve": [vp, vp, i32, vp, P(SolveReport)],
         "tp_step_opts_default": [P(StepOpts)],
@@ -217,6 +220,18 @@ def tp_fractional_apply(V, F, u, params: Optional[Params] = None):
     return Lu[:, 0] if squeeze else Lu
 
 
+def tp_sobolev_apply(V, F, u, params: Optional[Params] = None):
+    """A u = (B + B0) u, the operator of the inner product, for u of shape (nV,) or (nV, k)."""
+    V, F = _mesh(V, F)
+    squeeze = u.dim() == 1
+    u = _cols(u, V.shape[0], "u")
+    Au = torch.empty_like(u)
+    _check(lib().tp_sobolev_apply(V.data_ptr(), V.shape[0], F.data_ptr(), F.shape[0],
+                                  ctypes.byref(params or default_params()), u.data_ptr(),
+                                  u.shape[1], Au.data_ptr(), _stream()))
+    return Au[:, 0] if squeeze else Au
+
+
 def tp_precond_apply(V, F, b, params: Optional[Params] = None):
     V, F = _mesh(V, F)
     squeeze = b.dim() == 1
@@ -295,6 +310,13 @@ class Problem:
         Lu = out if out is not None else torch.empty_like(u)
         _check(lib().tp_problem_fractional_apply(self._h, u.data_ptr(), u.shape[1], Lu.data_ptr()))
         return Lu[:, 0] if squeeze else Lu
+
+    def sobolev_apply(self, u, out=None):
+        squeeze = u.dim() == 1
+        u = _cols(u, self.nV, "u")
+        Au = out if out is not None else torch.empty_like(u)
+        _check(lib().tp_problem_sobolev_apply(self._h, u.data_ptr(), u.shape[1], Au.data_ptr()))
+        return Au[:, 0] if squeeze else Au
 
     def precond_apply(self, b, out=None, allow_not_converged=False):
         squeeze = b.dim() == 1

@@ -460,3 +460,72 @@ def test_pcg_columns_together_like_alone(tp, torus40k):
     print(f"[pcg] torus40k second-solve right-hand sides: alone {alone}, together {rep.cg_iters[0]}", flush=True)
     assert rep.cg_relres[0] <= 1e-10
     assert rep.cg_iters[0] <= max(alone) + 5
+
+
+# ---------------------------------------------------- inner-product operator A = B + B0
+
+S_SOB = 5.0 / 3.0   # s = (beta - 2) / alpha for alpha = 6, beta = 12
+
+
+@pytest.mark.parametrize("k", [1, 3, 4, 7])
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_sobolev_parity(tp, meshes, k, prec):
+    """A u on a 1702-face torus (ragged last tile) against the oracle, column by column;
+    k = 4 and 7 take more than one group of three columns."""
+    m = meshes["torus37x23"]
+    print(f"[parity] sobolev k={k} precision={prec}", flush=True)
+    u = mg.random_columns(m.nV, k, 7)
+    A0 = O.sobolev_apply(m.V, m.F, u, S_SOB)
+    A1 = tp.tp_sobolev_apply(dev(m.V), dev(m.F, torch.int32), dev(u), tp.default_params(precision=prec))
+    A1 = A1.cpu().numpy()
+    errs = [rel(A1[:, c], A0[:, c]) for c in range(k)]
+    print("  errors", ["%.2e" % e for e in errs], flush=True)
+    assert max(errs) <= tol_for(prec), errs
+
+
+@pytest.mark.parametrize("name", ["small_sphere", "linked_small", "icosahedron", "geodesic9"])
+def test_sobolev_coordinates(tp, meshes, name):
+    """A applied to the coordinate functions (the operator A_3 of the descent direction acts
+    on them) and to constants (annihilated)."""
+    m = meshes[name]
+    print(f"[parity] sobolev coordinates {name}", flush=True)
+    u = np.ascontiguousarray(m.V)
+    A0 = O.sobolev_apply(m.V, m.F, u, S_SOB)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        A1 = P.sobolev_apply(dev(u)).cpu().numpy()
+        c1 = P.sobolev_apply(torch.ones((m.nV, 2), dtype=torch.float64, device="cuda")).cpu().numpy()
+    for c in range(3):
+        assert rel(A1[:, c], A0[:, c]) <= TOL32, (c, rel(A1[:, c], A0[:, c]))
+    assert np.abs(c1).max() <= 1e-6 * np.abs(A0).max()
+
+
+def test_sobolev_torus40k_sampled(tp, torus40k):
+    """The 40,000-face torus with three columns (one launch of the pair kernel, the
+    configuration the benchmark times): sampled vertices against the oracle; symmetry
+    u^T A v = v^T A u and A 1 = 0 at full size."""
+    m = torus40k
+    print("[parity] sobolev torus40k", flush=True)
+    u = mg.random_columns(m.nV, 3, 3)
+    v = mg.random_columns(m.nV, 3, 4)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        Au = P.sobolev_apply(dev(u)).cpu().numpy()
+        Av = P.sobolev_apply(dev(v)).cpu().numpy()
+        A1 = P.sobolev_apply(torch.ones((m.nV, 1), dtype=torch.float64, device="cuda")).cpu().numpy()
+    verts = np.random.default_rng(1).choice(m.nV, 24, replace=False)
+    A0 = O.sobolev_at_vertices(m.V, m.F, u, verts, S_SOB)
+    assert rel(Au[verts], A0) <= TOL32, rel(Au[verts], A0)
+    for c in range(3):
+        a, b = float(v[:, c] @ Au[:, c]), float(u[:, c] @ Av[:, c])
+        scale = np.linalg.norm(v[:, c]) * np.linalg.norm(Au[:, c])
+        assert abs(a - b) <= TOL32 * scale, (c, a, b, scale)
+    assert np.abs(A1).max() <= 1e-6 * np.abs(Au).max()
+
+
+def test_sobolev_errors(tp, meshes):
+    m = meshes["small_sphere"]
+    V, F = dev(m.V), dev(m.F, torch.int32)
+    with tp.Problem(V, F) as P:
+        for k in (0, 65):
+            st = tp.lib().tp_problem_sobolev_apply(P._h, V.data_ptr(), k, V.data_ptr())
+            assert st == 1, st
+        assert tp.lib().tp_problem_sobolev_apply(P._h, None, 3, V.data_ptr()) == 1
