@@ -173,6 +173,43 @@ TP_API tp_status tp_problem_energy(tp_problem* prob, double* E_out);
 TP_API tp_status tp_problem_gradient(tp_problem* prob, double* E_out, double* dE_out);
 TP_API tp_status tp_problem_fractional_apply(tp_problem* prob, const double* u, int k, double* Lu_out);
 TP_API tp_status tp_problem_sobolev_apply(tp_problem* prob, const double* u, int k, double* Au_out);
+
+/* Report of one GMRES solve with A (tp_problem_sobolev_solve). */
+typedef struct {
+    int    iters;             /* GMRES iterations (one preconditioner and one A product each) */
+    int    cycles;            /* restart cycles started                                       */
+    double relres;            /* largest |P b - A x| / |P b| over the columns (true residual) */
+    int    precond_cg_iters;  /* CG iterations summed over the preconditioner's Poisson solves */
+    double t_ms;              /* device time of the whole solve                                */
+    double omega;             /* weight of the diagonal term (precond = 1), else 0             */
+} tp_gmres_report;
+
+/* x = A^+ P b columnwise, A = B + B0 as in tp_sobolev_apply: the solve of the descent step
+ * done with the true operator (Sec. 5.4, step 3: an iterative method with the preconditioner
+ * of Sec. 5.2 and a zero initial guess; products with A evaluated directly rather than with
+ * the block cluster tree).  A annihilates the global constants only: its low-order term
+ * couples the connected components.  P subtracts the global mean and x has global mean
+ * zero; with 2 to 16 components the preconditioner is completed by an exact coarse solve
+ * on the component indicators (their relative translations), with more than 16 P
+ * subtracts every component's mean and x solves P A x = P b on that subspace (relative
+ * translations left out).  Right-preconditioned GMRES
+ * restarted every `restart` iterations, preconditioner A~^{-1} (tp_problem_precond_apply)
+ * kept per iteration (flexible form, since it is applied through CG solves); the k columns
+ * are independent systems iterated together.  Stops when every column's true residual
+ * |P b - A x| / |P b| <= rtol, or after maxiter iterations (TP_E_NOT_CONVERGED; x and the
+ * report are written).  With FP32 pair terms the residual is that of the FP32 operator,
+ * which is reproducible but not exact: rtol near 1e-7 and below needs TP_PREC_FP64.
+ * precond = 0: the preconditioner of Sec. 5.2 alone.  precond = 1: A~^{-1} + omega diag(A)^{-1},
+ * an addition to the paper: A~^{-1} under-weights the highest frequencies (its face
+ * averages lose them; the eigenvalue spread of A~^{-1} A grows about fourfold per halving
+ * of the edge length), which the diagonal of A (without the pairs of faces sharing the
+ * vertex) covers; omega = w^T A~^{-1} w / w^T v with w = A v on the coordinate functions.
+ * b, x_out: device, nV x k row-major double; b is not modified.  Requires rtol > 0,
+ * 1 <= restart <= 100, (restart + 1) k <= 1024, maxiter >= 1, precond 0 or 1
+ * (TP_E_INVALID_ARGUMENT).
+ * Device memory: 2 (restart + 1) nV k doubles of Krylov vectors, held by the problem. */
+TP_API tp_status tp_problem_sobolev_solve(tp_problem* prob, const double* b, int k, double rtol, int restart,
+                                          int maxiter, int precond, double* x_out, tp_gmres_report* report);
 TP_API tp_status tp_problem_precond_apply(tp_problem* prob, const double* b, int k, double* x_out,
                                    tp_solve_report* report);
 

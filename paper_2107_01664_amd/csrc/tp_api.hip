@@ -250,6 +250,10 @@ struct tp_problem {
 
     // work
     DevBuf<double> part, gface, zbuf, scal, red, vol6, edge;
+    // GMRES on A = B + B0: Krylov blocks V, Z, work vectors, small device arrays
+    DevBuf<double> gm_V, gm_Z, gm_w, gm_b, gm_r, gm_x, gm_small, gm_red, gm_Q, gm_Qn, gm_AQ, gm_one, gm_dinv,
+        gm_sv, gm_sw, gm_smw;
+    DevBuf<int32_t> gm_lab0;
     DevBuf<char> ub;
     DevBuf<double> cg_Z, cg_p, cg_red, cg_relres;
     DevBuf<unsigned> cg_bar;
@@ -297,6 +301,9 @@ struct tp_problem {
              pcg_rslot.bytes() + pcg_eslot.bytes() + pcg_phi.bytes() + pcg_rw.bytes() + pcg_esum.bytes() +
              pcg_Binv.bytes() + pcg_pval.bytes() + pcg_C0inv.bytes() + pcg_Vb.bytes() +
              pcg_rho.bytes() + pcg_red.bytes() + pcg_bp.bytes() + pcg_xp.bytes();
+        b += gm_V.bytes() + gm_Z.bytes() + gm_w.bytes() + gm_b.bytes() + gm_r.bytes() + gm_x.bytes() +
+             gm_small.bytes() + gm_red.bytes() + gm_Q.bytes() + gm_Qn.bytes() + gm_AQ.bytes() + gm_one.bytes() +
+             gm_lab0.bytes() + gm_dinv.bytes() + gm_sv.bytes() + gm_sw.bytes() + gm_smw.bytes();
         b += ml_r.bytes() + ml_p.bytes() + ml_s.bytes() + ml_m.bytes() + ml_an.bytes() + ml_v.bytes() +
              ml_shares.bytes() + ml_g.bytes() + ml_part.bytes() + ml_state.bytes();
         b += part.bytes() + gface.bytes() + zbuf.bytes() + scal.bytes() + red.bytes() + vol6.bytes() +
@@ -1326,6 +1333,334 @@ tp_status run_sobolev(tp_problem* P, const double* u, int ldu, int k, double* Au
     return TP_OK;
 }
 
+// x = A^+ P b columnwise by right-preconditioned GMRES(m) on A = B + B0 with the
+// preconditioner A~^{-1} of Sec. 5.2 and a zero initial guess (Sec. 5.4, step 3a).  The
+// preconditioner is applied through CG solves, so the directions it returns are kept (Z)
+// and the solution is formed from them (the flexible form of GMRES).  The k columns run in
+// lockstep, each with its own Krylov space, Hessenberg matrix and stopping test; classical
+// Gram-Schmidt with one re-orthogonalization pass.  A cycle ends after m iterations or when
+// every column's residual estimate is below rtol; the true residual P b - A x is then
+// formed, and a new cycle starts from it unless it is below rtol or maxiter iterations have
+// been spent.
+//
+// A annihilates the constants, and with several connected components only the global ones:
+// the low-order term B0 couples the components (ubar(S) - ubar(T) = 1 across two of them),
+// while the preconditioner annihilates each component's constants.  So P here subtracts the
+// global mean, and with 2..kGmCoarseMax components the preconditioner gains the coarse term
+// Q G^+ Q^T on the component indicators Q (G = Q^T A Q, inverted on the complement of the
+// global constant as G + tr(G)/nc e e^T): the relative translations of the components are
+// then solved for exactly.  With more components than that, P subtracts every component's
+// mean and the solve is the Galerkin one on that subspace (no relative translations).
+//
+// precond = 1 adds omega diag(A)^{-1} to the preconditioner.  A~^{-1} alone under-weights
+// the highest frequencies, where the face averages of L^sigma lose them (the spread of the
+// eigenvalues of A~^{-1} A grows about fourfold per halving of the edge length), while the
+// diagonal of A is accurate exactly there; omega matches the two on smooth functions:
+// omega = w^T A~^{-1} w / w^T v with w = A v, v the coordinate functions (averaged over
+// the three).  The diagonal is taken without the pairs of faces that share the vertex.
+constexpr int kGmCoarseMax = 16;
+
+tp_status run_precond(tp_problem* P, const double* b, int k, double* x, tp_solve_report* rep);
+
+tp_status run_sobolev_solve(tp_problem* P, const double* b, int k, double rtol, int m, int maxiter, int precond,
+                            double* x, tp_gmres_report* rep)
+{
+    hipStream_t s = P->stream;
+    TP_TRY(ensure_geometry(P));
+    TP_TRY(ensure_lap(P));
+    TP_TRY(ensure_vf(P));
+    const int64_t n = P->nV;
+    const size_t nk = (size_t)n * k;
+    const int64_t vs = (int64_t)nk;
+    TP_TRY(P->gm_V.ensure((size_t)(m + 1) * nk, s));
+    TP_TRY(P->gm_Z.ensure((size_t)m * nk, s));
+    TP_TRY(P->gm_w.ensure(nk, s));
+    TP_TRY(P->gm_b.ensure(nk, s));
+    TP_TRY(P->gm_r.ensure(nk, s));
+    TP_TRY(P->gm_x.ensure(nk, s));
+    // h1 [(m+1) k], h2 [(m+1) k], norms [k], scale [k], y [m k]
+    const size_t o_h1 = 0, o_h2 = (size_t)(m + 1) * k, o_nrm = 2 * (size_t)(m + 1) * k, o_sc = o_nrm + k,
+                 o_y = o_sc + k;
+    const int nc = P->ncomp;
+    const bool coarse = nc > 1 && nc <= kGmCoarseMax;
+    const size_t o_cq = o_y + (size_t)m * k, o_cy = o_cq + (size_t)nc * k, o_om = o_cy + (size_t)nc * k;
+    TP_TRY(P->gm_small.ensure(o_om + 6, s));
+    TP_TRY(P->gm_red.ensure(std::max(krylov_scratch_doubles((m + 1) * k),
+                                     project_scratch_doubles(k, P->ncomp)), s));
+    double* sm = P->gm_small.p;
+    EventTimer tm(s);
+    tm.mark(0);
+    std::vector<double> Gchol;   // Cholesky factor (lower, row-major) of G + tr(G)/nc e e^T
+    if (coarse) {
+        TP_TRY(P->gm_lab0.ensure((size_t)n, s));
+        TP_TRY(P->gm_one.ensure(1, s));
+        TP_HIP(hipMemsetAsync(P->gm_lab0.p, 0, sizeof(int32_t) * (size_t)n, s));
+        const double invn = 1.0 / (double)n;
+        TP_HIP(hipMemcpyAsync(P->gm_one.p, &invn, sizeof(double), hipMemcpyHostToDevice, s));
+        TP_TRY(P->gm_Q.ensure((size_t)nc * nk, s));
+        TP_TRY(P->gm_Qn.ensure((size_t)n * nc, s));
+        TP_TRY(P->gm_AQ.ensure((size_t)n * nc, s));
+        // gm_Q: nc blocks of n x k, block l the indicator of component l in every column;
+        // gm_Qn: one n x nc matrix whose column l is the indicator of component l
+        TP_HIP(krylov_indicators(P->comp.p, n, nc, k, P->gm_Q.p, s));
+        std::vector<int32_t> lab((size_t)n);
+        TP_HIP(hipMemcpyAsync(lab.data(), P->comp.p, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        std::vector<double> qn((size_t)n * nc, 0.0), aq((size_t)n * nc);
+        for (int64_t v = 0; v < n; ++v)
+            if (lab[v] >= 0 && lab[v] < nc) qn[(size_t)v * nc + lab[v]] = 1.0;
+        TP_HIP(hipMemcpyAsync(P->gm_Qn.p, qn.data(), sizeof(double) * qn.size(), hipMemcpyHostToDevice, s));
+        TP_TRY(run_sobolev(P, P->gm_Qn.p, nc, nc, P->gm_AQ.p, nc));
+        TP_HIP(hipMemcpyAsync(aq.data(), P->gm_AQ.p, sizeof(double) * aq.size(), hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        std::vector<double> G((size_t)nc * nc, 0.0);   // G[i][l] = q_i^T A q_l, rows in vertex order
+        for (int64_t v = 0; v < n; ++v)
+            if (lab[v] >= 0 && lab[v] < nc)
+                for (int l = 0; l < nc; ++l) G[(size_t)lab[v] * nc + l] += aq[(size_t)v * nc + l];
+        double tr = 0.0;
+        for (int i = 0; i < nc; ++i) tr += G[(size_t)i * nc + i];
+        if (!(tr > 0.0)) return fail(TP_E_NONFINITE, "component coupling matrix is not positive");
+        std::vector<double> Gs((size_t)nc * nc);
+        for (int i = 0; i < nc; ++i)
+            for (int l = 0; l < nc; ++l)
+                Gs[(size_t)i * nc + l] = 0.5 * (G[(size_t)i * nc + l] + G[(size_t)l * nc + i]) + tr / nc;
+        Gchol.assign((size_t)nc * nc, 0.0);
+        for (int i = 0; i < nc; ++i)
+            for (int l = 0; l <= i; ++l) {
+                double acc = Gs[(size_t)i * nc + l];
+                for (int q = 0; q < l; ++q) acc -= Gchol[(size_t)i * nc + q] * Gchol[(size_t)l * nc + q];
+                if (i == l) {
+                    if (!(acc > 0.0)) return fail(TP_E_NONFINITE, "component coupling matrix is singular");
+                    Gchol[(size_t)i * nc + i] = std::sqrt(acc);
+                } else {
+                    Gchol[(size_t)i * nc + l] = acc / Gchol[(size_t)l * nc + l];
+                }
+            }
+        TP_TRY(P->gm_red.ensure(std::max({krylov_scratch_doubles((m + 1) * k), krylov_scratch_doubles(nc * k),
+                                          project_scratch_doubles(k, P->ncomp)}), s));
+    }
+    double omega = 0.0;
+    if (precond == 1) {
+        // approximate diagonal: row sums of the two kernel matrices, then the vertex sums
+        SobolevCall c;
+        c.fd = &P->fd;
+        c.plan = sobolev_plan(TP_PREC_FP32_HILO, 1, P->nF, P->cap);
+        c.precision = TP_PREC_FP32_HILO;
+        c.s = (P->prm.beta - 2.0) / P->prm.alpha;
+        c.V = P->V.p;
+        c.F = P->F.p;
+        c.nV = P->nV;
+        c.nF = P->nF;
+        c.vf_off = P->vf_off.p;
+        c.vf_idx = P->vf_idx.p;
+        TP_TRY(P->part.ensure((size_t)c.plan.n_split * 4 * c.plan.irows, s));
+        TP_TRY(P->zbuf.ensure((size_t)4 * c.plan.irows, s));
+        TP_TRY(P->gm_dinv.ensure((size_t)n, s));
+        c.part = P->part.p;
+        c.z = P->zbuf.p;
+        TP_HIP(launch_sobolev_diag(c, P->gm_dinv.p, s));
+        // omega from the coordinate functions
+        const size_t n3 = (size_t)n * 3;
+        TP_TRY(P->gm_sv.ensure(n3, s));
+        TP_TRY(P->gm_sw.ensure(n3, s));
+        TP_TRY(P->gm_smw.ensure(n3, s));
+        TP_TRY(P->red.ensure(std::max(reduce_scratch_doubles(16), project_scratch_doubles(3, P->ncomp)), s));
+        TP_HIP(hipMemcpyAsync(P->gm_sv.p, P->V.p, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+        TP_HIP(launch_project_mean(P->gm_sv.p, 3, 3, n, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
+        TP_TRY(run_sobolev(P, P->gm_sv.p, 3, 3, P->gm_sw.p, 3));
+        tp_solve_report prep;
+        TP_TRY(run_precond(P, P->gm_sw.p, 3, P->gm_smw.p, &prep));
+        TP_HIP(launch_dot_cols(P->gm_sw.p, 3, P->gm_smw.p, 3, n, 3, P->red.p, sm + o_om, s));
+        TP_HIP(launch_dot_cols(P->gm_sw.p, 3, P->gm_sv.p, 3, n, 3, P->red.p, sm + o_om + 3, s));
+        double nd[6];
+        TP_HIP(hipMemcpyAsync(nd, sm + o_om, sizeof(nd), hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        int cnt = 0;
+        for (int q = 0; q < 3; ++q)
+            if (nd[3 + q] > 0.0 && nd[q] > 0.0) {
+                omega += nd[q] / nd[3 + q];
+                ++cnt;
+            }
+        if (cnt == 0) return fail(TP_E_NONFINITE, "no positive Rayleigh quotient for the diagonal weight");
+        omega /= cnt;
+    }
+    const int32_t* plab = coarse ? P->gm_lab0.p : P->comp.p;
+    const double* pinv = coarse ? P->gm_one.p : P->inv_count.p;
+    const int pnc = coarse ? 1 : nc;
+    auto project = [&](double* v) -> tp_status {
+        TP_HIP(launch_project_mean(v, k, k, n, plab, pinv, pnc, P->gm_red.p, s));
+        return TP_OK;
+    };
+    // Z += Q G^+ Q^T V (the coarse term), columnwise
+    std::vector<double> qtv((size_t)nc * k), ycoef((size_t)nc * k), tv(nc);
+    auto coarse_add = [&](const double* Vj, double* Zj) -> tp_status {
+        TP_HIP(krylov_dots(P->gm_Q.p, vs, nc, Vj, n, k, P->gm_red.p, sm + o_cq, s));
+        TP_HIP(hipMemcpyAsync(qtv.data(), sm + o_cq, sizeof(double) * nc * k, hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        for (int c = 0; c < k; ++c) {
+            for (int i = 0; i < nc; ++i) {   // forward substitution
+                double acc = qtv[(size_t)i * k + c];
+                for (int q = 0; q < i; ++q) acc -= Gchol[(size_t)i * nc + q] * tv[q];
+                tv[i] = acc / Gchol[(size_t)i * nc + i];
+            }
+            for (int i = nc - 1; i >= 0; --i) {   // back substitution with the transpose
+                double acc = tv[i];
+                for (int q = i + 1; q < nc; ++q) acc -= Gchol[(size_t)q * nc + i] * ycoef[(size_t)q * k + c];
+                ycoef[(size_t)i * k + c] = acc / Gchol[(size_t)i * nc + i];
+            }
+        }
+        TP_HIP(hipMemcpyAsync(sm + o_cy, ycoef.data(), sizeof(double) * nc * k, hipMemcpyHostToDevice, s));
+        TP_HIP(krylov_combine(Zj, P->gm_Q.p, vs, nc, sm + o_cy, n, k, true, s));
+        return TP_OK;
+    };
+    auto col_norms = [&](const double* v, std::vector<double>& out) -> tp_status {
+        TP_HIP(krylov_dots(v, vs, 1, v, n, k, P->gm_red.p, sm + o_nrm, s));
+        out.assign(k, 0.0);
+        TP_HIP(hipMemcpyAsync(out.data(), sm + o_nrm, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        for (double& v2 : out) v2 = std::sqrt(std::max(v2, 0.0));
+        return TP_OK;
+    };
+    // P b, its norms, x = 0, r = P b
+    TP_HIP(hipMemcpyAsync(P->gm_b.p, b, nk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    TP_TRY(project(P->gm_b.p));
+    std::vector<double> bnorm, beta, relres(k, 0.0);
+    TP_TRY(col_norms(P->gm_b.p, bnorm));
+    TP_HIP(hipMemsetAsync(P->gm_x.p, 0, nk * sizeof(double), s));
+    TP_HIP(hipMemcpyAsync(P->gm_r.p, P->gm_b.p, nk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    beta = bnorm;
+    int total = 0, cycles = 0, pc_iters = 0;
+    bool converged = false;
+    std::vector<double> h1((size_t)(m + 1) * k), h2((size_t)(m + 1) * k), nrm2(k), scale(k), Y((size_t)m * k);
+    for (;;) {
+        // stopping test on the true residual
+        bool all_done = true;
+        for (int c = 0; c < k; ++c) {
+            relres[c] = bnorm[c] > 0.0 ? beta[c] / bnorm[c] : 0.0;
+            if (relres[c] > rtol) all_done = false;
+        }
+        if (all_done) {
+            converged = true;
+            break;
+        }
+        if (total >= maxiter) break;
+        ++cycles;
+        // V0 = r / beta for the columns still above the tolerance, 0 for the others
+        std::vector<char> live(k, 0);
+        for (int c = 0; c < k; ++c) {
+            live[c] = relres[c] > rtol;
+            scale[c] = live[c] ? 1.0 / beta[c] : 0.0;
+        }
+        TP_HIP(hipMemcpyAsync(sm + o_sc, scale.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+        TP_HIP(krylov_scale(P->gm_V.p, P->gm_r.p, sm + o_sc, n, k, s));
+        std::vector<std::vector<double>> H(k, std::vector<double>((size_t)(m + 1) * m, 0.0));
+        std::vector<std::vector<double>> g(k, std::vector<double>(m + 1, 0.0)), cs(k, std::vector<double>(m, 0.0)),
+            sn(k, std::vector<double>(m, 0.0));
+        std::vector<int> used(k, 0);
+        for (int c = 0; c < k; ++c) g[c][0] = live[c] ? beta[c] : 0.0;
+        int j = 0;
+        for (; j < m && total < maxiter; ++j) {
+            bool any = false;
+            for (int c = 0; c < k; ++c) any = any || live[c];
+            if (!any) break;
+            double* Vj = P->gm_V.p + (size_t)j * nk;
+            double* Zj = P->gm_Z.p + (size_t)j * nk;
+            tp_solve_report prep;
+            TP_TRY(run_precond(P, Vj, k, Zj, &prep));
+            pc_iters += prep.cg_iters[0] + prep.cg_iters[1];
+            if (precond == 1) {
+                TP_HIP(krylov_diag_add(Zj, Vj, P->gm_dinv.p, omega, n, k, s));
+                // keep the directions in the solution space (mean zero, per component when
+                // the component translations are left out)
+                if (!coarse) TP_TRY(project(Zj));
+            }
+            if (coarse) TP_TRY(coarse_add(Vj, Zj));
+            TP_TRY(run_sobolev(P, Zj, k, k, P->gm_w.p, k));
+            TP_TRY(project(P->gm_w.p));
+            TP_HIP(krylov_dots(P->gm_V.p, vs, j + 1, P->gm_w.p, n, k, P->gm_red.p, sm + o_h1, s));
+            TP_HIP(krylov_subtract(P->gm_w.p, P->gm_V.p, vs, j + 1, sm + o_h1, n, k, s));
+            TP_HIP(krylov_dots(P->gm_V.p, vs, j + 1, P->gm_w.p, n, k, P->gm_red.p, sm + o_h2, s));
+            TP_HIP(krylov_subtract(P->gm_w.p, P->gm_V.p, vs, j + 1, sm + o_h2, n, k, s));
+            TP_HIP(krylov_dots(P->gm_w.p, vs, 1, P->gm_w.p, n, k, P->gm_red.p, sm + o_nrm, s));
+            TP_HIP(hipMemcpyAsync(h1.data(), sm + o_h1, sizeof(double) * (j + 1) * k, hipMemcpyDeviceToHost, s));
+            TP_HIP(hipMemcpyAsync(h2.data(), sm + o_h2, sizeof(double) * (j + 1) * k, hipMemcpyDeviceToHost, s));
+            TP_HIP(hipMemcpyAsync(nrm2.data(), sm + o_nrm, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+            TP_HIP(hipStreamSynchronize(s));
+            ++total;
+            for (int c = 0; c < k; ++c) {
+                scale[c] = 0.0;
+                if (!live[c]) continue;
+                double* Hc = H[c].data() + (size_t)j * (m + 1);   // column j, rows 0..j+1
+                for (int i = 0; i <= j; ++i) Hc[i] = h1[(size_t)i * k + c] + h2[(size_t)i * k + c];
+                const double hn = std::sqrt(std::max(nrm2[c], 0.0));
+                Hc[j + 1] = hn;
+                for (int i = 0; i < j; ++i) {   // earlier rotations
+                    const double a = Hc[i], bb = Hc[i + 1];
+                    Hc[i] = cs[c][i] * a + sn[c][i] * bb;
+                    Hc[i + 1] = -sn[c][i] * a + cs[c][i] * bb;
+                }
+                const double den = std::hypot(Hc[j], Hc[j + 1]);
+                cs[c][j] = den > 0.0 ? Hc[j] / den : 1.0;
+                sn[c][j] = den > 0.0 ? Hc[j + 1] / den : 0.0;
+                Hc[j] = den;
+                Hc[j + 1] = 0.0;
+                g[c][j + 1] = -sn[c][j] * g[c][j];
+                g[c][j] = cs[c][j] * g[c][j];
+                used[c] = j + 1;
+                const double est = std::fabs(g[c][j + 1]);
+                if (est <= rtol * bnorm[c] || hn <= 0.0) live[c] = 0;
+                else scale[c] = 1.0 / hn;
+            }
+            TP_HIP(hipMemcpyAsync(sm + o_sc, scale.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+            TP_HIP(krylov_scale(P->gm_V.p + (size_t)(j + 1) * nk, P->gm_w.p, sm + o_sc, n, k, s));
+        }
+        // y = R^{-1} g per column, x += Z y
+        int nv = 0;
+        std::fill(Y.begin(), Y.end(), 0.0);
+        for (int c = 0; c < k; ++c) {
+            const int u = used[c];
+            nv = std::max(nv, u);
+            for (int i = u - 1; i >= 0; --i) {
+                double acc = g[c][i];
+                for (int q = i + 1; q < u; ++q) acc -= H[c][(size_t)q * (m + 1) + i] * Y[(size_t)q * k + c];
+                const double d = H[c][(size_t)i * (m + 1) + i];
+                Y[(size_t)i * k + c] = d != 0.0 ? acc / d : 0.0;
+            }
+        }
+        if (nv > 0) {
+            TP_HIP(hipMemcpyAsync(sm + o_y, Y.data(), sizeof(double) * (size_t)nv * k, hipMemcpyHostToDevice, s));
+            TP_HIP(krylov_combine(P->gm_x.p, P->gm_Z.p, vs, nv, sm + o_y, n, k, true, s));
+        }
+        // true residual r = P b - A x
+        TP_TRY(run_sobolev(P, P->gm_x.p, k, k, P->gm_w.p, k));
+        TP_TRY(project(P->gm_w.p));
+        for (int c = 0; c < k; ++c) scale[c] = 1.0;
+        TP_HIP(hipMemcpyAsync(sm + o_sc, scale.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+        TP_HIP(hipMemcpyAsync(P->gm_r.p, P->gm_b.p, nk * sizeof(double), hipMemcpyDeviceToDevice, s));
+        TP_HIP(krylov_subtract(P->gm_r.p, P->gm_w.p, vs, 1, sm + o_sc, n, k, s));
+        TP_TRY(col_norms(P->gm_r.p, beta));
+        if (nv == 0) {   // no progress possible (every column stopped on a breakdown)
+            for (int c = 0; c < k; ++c) relres[c] = bnorm[c] > 0.0 ? beta[c] / bnorm[c] : 0.0;
+            break;
+        }
+    }
+    TP_TRY(project(P->gm_x.p));   // the representative with mean zero
+    TP_HIP(hipMemcpyAsync(x, P->gm_x.p, nk * sizeof(double), hipMemcpyDeviceToDevice, s));
+    tm.mark(1);
+    if (rep) {
+        std::memset(rep, 0, sizeof(*rep));
+        rep->iters = total;
+        rep->cycles = cycles;
+        rep->relres = *std::max_element(relres.begin(), relres.end());
+        rep->precond_cg_iters = pc_iters;
+        rep->t_ms = tm.ms(0, 1);
+        rep->omega = omega;
+    }
+    TP_HIP(hipStreamSynchronize(s));
+    if (!converged) return fail(TP_E_NOT_CONVERGED, "GMRES did not reach the tolerance within maxiter iterations");
+    return TP_OK;
+}
+
 // x = C^+ b for k columns (row stride k); b is overwritten with its projection.
 tp_status run_cg(tp_problem* P, double* b, double* x, int k, int* it_max, double* res_max)
 {
@@ -2016,6 +2351,19 @@ tp_status tp_problem_sobolev_apply(tp_problem* P, const double* u, int k, double
     TP_TRY(run_sobolev(P, u, k, k, Au_out, k));
     TP_HIP(hipStreamSynchronize(P->stream));
     return TP_OK;
+}
+
+tp_status tp_problem_sobolev_solve(tp_problem* P, const double* b, int k, double rtol, int restart,
+                                   int maxiter, int precond, double* x_out, tp_gmres_report* report)
+{
+    TP_TRY(bind(P));
+    if (!b || !x_out) return fail(TP_E_INVALID_ARGUMENT, "b and x_out must be non-NULL");
+    if (k < 1 || k > kMaxCols) return fail(TP_E_INVALID_ARGUMENT, "k must lie in [1, 64]");
+    if (!(rtol > 0.0) || restart < 1 || restart > 100 || maxiter < 1 || (restart + 1) * k > 1024)
+        return fail(TP_E_INVALID_ARGUMENT, "need rtol > 0, 1 <= restart <= 100, (restart + 1) k <= 1024, maxiter >= 1");
+    if (precond != 0 && precond != 1) return fail(TP_E_INVALID_ARGUMENT, "precond must be 0 or 1");
+    set_error("");
+    return run_sobolev_solve(P, b, k, rtol, restart, maxiter, precond, x_out, report);
 }
 
 tp_status tp_problem_precond_apply(tp_problem* P, const double* b, int k, double* x_out,

@@ -101,7 +101,7 @@ __global__ void k_sob_face(const double* __restrict__ V, const int32_t* __restri
 
 // ------------------------------------------------------------------ FP32 pair sums
 
-template <bool DIAG, int NI, int KC, bool HILO>
+template <bool DIAG, int NI, int KC, bool HILO, bool ROWSUM>
 __device__ __forceinline__ void sob_tile32(const float4* s_x, const float4* s_l, const float4* s_n,
                                            const float4* s_u, int64_t j0, const float3 (&Sh)[NI],
                                            const float3 (&Sl)[NI], const float3 (&Sn)[NI],
@@ -134,6 +134,11 @@ __device__ __forceinline__ void sob_tile32(const float4* s_x, const float4* s_l,
             const float qt = tn.x * dx + tn.y * dy + tn.z * dz;
             const float inv = __builtin_amdgcn_rcpf(r2);
             const float w0 = w * ((qs * qs + qt * qt) * (inv * inv));
+            if (ROWSUM) {   // the row sums of both kernel matrices (weights a_T included)
+                c[r][0] += DIAG && Si[r] == j0 + jj ? 0.f : w;
+                c[r][3] += w0;
+                continue;
+            }
 #pragma unroll
             for (int cc = 0; cc < KC; ++cc) {
                 c[r][4 * cc + 0] += w * (Su[r][cc].x - tu[cc].x);
@@ -145,7 +150,7 @@ __device__ __forceinline__ void sob_tile32(const float4* s_x, const float4* s_l,
     }
 }
 
-template <int NI, int KC, bool HILO>
+template <int NI, int KC, bool HILO, bool ROWSUM = false>
 __global__ __launch_bounds__(kBlock) void k_sob32(SobArgs A, float ms)
 {
     const int bi = (int)blockIdx.x % A.n_itiles;
@@ -175,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void k_sob32(SobArgs A, float ms)
             Sl[r] = make_float3(0.f, 0.f, 0.f);
         }
 #pragma unroll
-        for (int cc = 0; cc < KC; ++cc) Su[r][cc] = fu[Si[r] * KC + cc];
+        for (int cc = 0; cc < KC; ++cc) Su[r][cc] = ROWSUM ? make_float4(0.f, 0.f, 0.f, 0.f) : fu[Si[r] * KC + cc];
 #pragma unroll
         for (int q = 0; q < 4 * KC; ++q) acc[r][q] = 0.0;
     }
@@ -187,7 +192,8 @@ __global__ __launch_bounds__(kBlock) void k_sob32(SobArgs A, float ms)
             s_n[e] = fn[j0 + e];
             if (HILO) s_l[e] = fl[j0 + e];
         }
-        for (int e = threadIdx.x; e < kTileJ * KC; e += kBlock) s_u[e] = fu[j0 * KC + e];
+        if (!ROWSUM)
+            for (int e = threadIdx.x; e < kTileJ * KC; e += kBlock) s_u[e] = fu[j0 * KC + e];
         __syncthreads();
         float c[NI][4 * KC];
 #pragma unroll
@@ -195,9 +201,9 @@ __global__ __launch_bounds__(kBlock) void k_sob32(SobArgs A, float ms)
 #pragma unroll
             for (int q = 0; q < 4 * KC; ++q) c[r][q] = 0.f;
         if (hits_diag(j0, ibase, kBlock * NI))
-            sob_tile32<true, NI, KC, HILO>(s_x, s_l, s_n, s_u, j0, Sh, Sl, Sn, Su, Si, ms, c);
+            sob_tile32<true, NI, KC, HILO, ROWSUM>(s_x, s_l, s_n, s_u, j0, Sh, Sl, Sn, Su, Si, ms, c);
         else
-            sob_tile32<false, NI, KC, HILO>(s_x, s_l, s_n, s_u, j0, Sh, Sl, Sn, Su, Si, ms, c);
+            sob_tile32<false, NI, KC, HILO, ROWSUM>(s_x, s_l, s_n, s_u, j0, Sh, Sl, Sn, Su, Si, ms, c);
 #pragma unroll
         for (int r = 0; r < NI; ++r)
 #pragma unroll
@@ -297,6 +303,38 @@ __global__ void k_sob_gather(int64_t nV, const int32_t* __restrict__ vf_off, con
     Au[v * ldo + c0 + c] = acc;
 }
 
+// Approximate diagonal of A from the row sums rs(S) = sum_T |d|^-2s a_T and
+// r0(S) = sum_T |d|^-2s a_T (q_S^2 + q_T^2) / |d|^4 (z layout [4][irows]: rows 0 and 3):
+//   diag_i = 2 sum_{S ni i} a_S (|D phi_i(S)|^2 rs(S) + r0(S) / 18),
+// i.e. (A)_ii without the pairs S, T that both contain i (u = e_i has D u(T) = 0 and
+// ubar(T) = 0 on every other face).  dinv = 1 / diag.
+__global__ void k_sob_diag(int64_t nV, const int32_t* __restrict__ vf_off, const int32_t* __restrict__ vf_idx,
+                           const double* __restrict__ V, const int32_t* __restrict__ F,
+                           const double4* __restrict__ dxa, const double* __restrict__ z, int64_t zs,
+                           double* __restrict__ dinv)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nV) return;
+    double acc = 0.0;
+    for (int32_t q = vf_off[v]; q < vf_off[v + 1]; ++q) {
+        const int64_t f = vf_idx[q] / 3;
+        const int m = vf_idx[q] - 3 * (int)f;
+        const double* pi = V + 3 * (int64_t)F[3 * f + m];
+        const double* pj = V + 3 * (int64_t)F[3 * f + (m + 1) % 3];
+        const double* pk = V + 3 * (int64_t)F[3 * f + (m + 2) % 3];
+        const double e1[3] = {pj[0] - pi[0], pj[1] - pi[1], pj[2] - pi[2]};
+        const double e2[3] = {pk[0] - pi[0], pk[1] - pi[1], pk[2] - pi[2]};
+        const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2],
+                              e1[0] * e2[1] - e1[1] * e2[0]};
+        const double c2 = cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2];
+        const double e2n = (pk[0] - pj[0]) * (pk[0] - pj[0]) + (pk[1] - pj[1]) * (pk[1] - pj[1]) +
+                           (pk[2] - pj[2]) * (pk[2] - pj[2]);
+        // |c x e|^2 / |c|^4 = |e|^2 / |c|^2 (e lies in the face's plane, orthogonal to c)
+        acc += 2.0 * dxa[f].w * (e2n / c2 * z[f] + z[3 * zs + f] / 18.0);
+    }
+    dinv[v] = acc > 0.0 ? 1.0 / acc : 0.0;
+}
+
 // ------------------------------------------------------------------ dispatch
 
 const void* sob_fn(int precision, int kc)
@@ -355,6 +393,34 @@ size_t sobolev_face_bytes(int precision, int kc, int64_t cap)
     return (size_t)cap * (size_t)kc * (precision == TP_PREC_FP64 ? sizeof(double4) : sizeof(float4));
 }
 
+hipError_t launch_sobolev_diag(const SobolevCall& c, double* dinv, hipStream_t s)
+{
+    if (!c.fd) return hipErrorInvalidValue;
+    const FaceData& fd = *c.fd;
+    const PairPlan& pl = c.plan;
+    if (pl.irows > fd.cap || (int64_t)pl.ntiles_j * kTileJ > fd.cap) return hipErrorInvalidValue;
+    SobArgs A;
+    A.fx = fd.fx;
+    A.fl = fd.fl;
+    A.fn = fd.fn;
+    A.fu = nullptr;
+    A.part = c.part;
+    A.irows = pl.irows;
+    A.n_itiles = pl.n_itiles;
+    A.tiles_per_split = pl.tiles_per_split;
+    A.ntiles_j = pl.ntiles_j;
+    const dim3 grid((unsigned)(pl.n_itiles * pl.n_split)), block(kBlock);
+    // FP32 hi/lo pair terms whatever the problem's precision: the diagonal only preconditions
+    hipLaunchKernelGGL((k_sob32<kNiSob32, 1, true, true>), grid, block, 0, s, A, (float)-c.s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_reduce_splits(c.part, pl.n_split, 4, pl.irows, c.nF, c.z, pl.irows, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_sob_diag, dim3(nblk(c.nV)), dim3(256), 0, s, c.nV, c.vf_off, c.vf_idx, c.V, c.F, fd.dx,
+                       c.z, pl.irows, dinv);
+    return hipGetLastError();
+}
+
 hipError_t launch_sobolev(const SobolevCall& c, const double* u, int ldu, int kc, double* Au, int ldo,
                           int c0, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s)
 {
@@ -394,6 +460,141 @@ hipError_t launch_sobolev(const SobolevCall& c, const double* u, int ldu, int kc
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_sob_gather, dim3(nblk(c.nV * kc)), dim3(256), 0, s, c.nV, c.vf_off, c.vf_idx, c.V, c.F,
                        fd.dx, c.z, pl.irows, kc, ldo, c0, Au);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Krylov vectors
+
+namespace {
+
+constexpr int kKryBlocks = 256;   // workgroups of the first reduction stage
+constexpr int kKryMaxOut = 1024;  // outputs of one krylov_dots call (nvec * k)
+
+__global__ __launch_bounds__(256) void k_kry_dots(const double* __restrict__ Vb, int64_t vstride, int nvec,
+                                                  const double* __restrict__ w, int64_t n, int k,
+                                                  double* __restrict__ partial)
+{
+    // rows [b, e) of this workgroup; one thread per (row, column) element of the chunk
+    __shared__ double sh[4];
+    const int64_t chunk = (n + kKryBlocks - 1) / kKryBlocks;
+    const int64_t b = (int64_t)blockIdx.x * chunk, e = min(n, b + chunk);
+    const int m = nvec * k;
+    for (int o = 0; o < m; ++o) {
+        const int i = o / k, c = o - i * k;
+        const double* V = Vb + (int64_t)i * vstride;
+        double acc = 0.0;
+        for (int64_t r = b + threadIdx.x; r < e; r += 256) acc += V[r * k + c] * w[r * k + c];
+        for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) partial[(int64_t)blockIdx.x * m + o] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+        __syncthreads();
+    }
+}
+
+__global__ void k_kry_final(const double* __restrict__ partial, int m, double* __restrict__ out)
+{
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= m) return;
+    double acc = 0.0;
+    for (int q = 0; q < kKryBlocks; ++q) acc += partial[(int64_t)q * m + o];
+    out[o] = acc;
+}
+
+__global__ void k_kry_subtract(double* __restrict__ w, const double* __restrict__ Vb, int64_t vstride, int nvec,
+                               const double* __restrict__ h, int64_t n, int k)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    const int c = (int)(t % k);
+    double acc = w[t];
+    for (int i = 0; i < nvec; ++i) acc -= h[i * k + c] * Vb[(int64_t)i * vstride + t];
+    w[t] = acc;
+}
+
+__global__ void k_kry_combine(double* __restrict__ x, const double* __restrict__ Zb, int64_t vstride, int nvec,
+                              const double* __restrict__ y, int64_t n, int k, int accumulate)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    const int c = (int)(t % k);
+    double acc = accumulate ? x[t] : 0.0;
+    for (int i = 0; i < nvec; ++i) acc += y[i * k + c] * Zb[(int64_t)i * vstride + t];
+    x[t] = acc;
+}
+
+__global__ void k_kry_scale(double* __restrict__ dst, const double* __restrict__ src,
+                            const double* __restrict__ scale, int64_t n, int k)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    dst[t] = src[t] * scale[t % k];
+}
+
+__global__ void k_kry_diag_add(double* __restrict__ Z, const double* __restrict__ V,
+                               const double* __restrict__ dinv, double omega, int64_t n, int k)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * k) return;
+    Z[t] += omega * dinv[t / k] * V[t];
+}
+
+__global__ void k_kry_indicators(const int32_t* __restrict__ label, int64_t n, int nl, int width,
+                                 double* __restrict__ out)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = n * width;
+    if (t >= per * nl) return;
+    const int64_t l = t / per;
+    const int64_t v = (t - l * per) / width;
+    out[t] = label[v] == (int32_t)l ? 1.0 : 0.0;
+}
+
+}  // namespace
+
+hipError_t krylov_diag_add(double* Z, const double* V, const double* dinv, double omega, int64_t n, int k,
+                           hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kry_diag_add, dim3(nblk(n * k)), dim3(256), 0, s, Z, V, dinv, omega, n, k);
+    return hipGetLastError();
+}
+
+hipError_t krylov_indicators(const int32_t* label, int64_t n, int nl, int width, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kry_indicators, dim3(nblk(n * width * nl)), dim3(256), 0, s, label, n, nl, width, out);
+    return hipGetLastError();
+}
+
+size_t krylov_scratch_doubles(int m) { return (size_t)kKryBlocks * (size_t)std::max(1, m); }
+
+hipError_t krylov_dots(const double* Vb, int64_t vstride, int nvec, const double* w, int64_t n, int k,
+                       double* scratch, double* out, hipStream_t s)
+{
+    const int m = nvec * k;
+    if (nvec < 1 || k < 1 || m > kKryMaxOut) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_kry_dots, dim3(kKryBlocks), dim3(256), 0, s, Vb, vstride, nvec, w, n, k, scratch);
+    hipLaunchKernelGGL(k_kry_final, dim3(nblk(m)), dim3(256), 0, s, scratch, m, out);
+    return hipGetLastError();
+}
+
+hipError_t krylov_subtract(double* w, const double* Vb, int64_t vstride, int nvec, const double* h, int64_t n,
+                           int k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kry_subtract, dim3(nblk(n * k)), dim3(256), 0, s, w, Vb, vstride, nvec, h, n, k);
+    return hipGetLastError();
+}
+
+hipError_t krylov_combine(double* x, const double* Zb, int64_t vstride, int nvec, const double* y, int64_t n,
+                          int k, bool accumulate, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kry_combine, dim3(nblk(n * k)), dim3(256), 0, s, x, Zb, vstride, nvec, y, n, k,
+                       accumulate ? 1 : 0);
+    return hipGetLastError();
+}
+
+hipError_t krylov_scale(double* dst, const double* src, const double* scale, int64_t n, int k, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_kry_scale, dim3(nblk(n * k)), dim3(256), 0, s, dst, src, scale, n, k);
     return hipGetLastError();
 }
 

@@ -34,6 +34,7 @@ EXPORTED = [
     "tp_precond_apply", "tp_problem_create", "tp_problem_destroy", "tp_problem_set_vertices",
     "tp_problem_get_vertices", "tp_problem_energy", "tp_problem_gradient",
     "tp_problem_fractional_apply", "tp_sobolev_apply", "tp_problem_sobolev_apply",
+    "tp_problem_sobolev_solve",
     "tp_problem_precond_apply", "tp_step_opts_default",
     "tp_precond_step", "tp_last_error", "tp_profile_enable", "tp_profile_reset", "tp_profile_get",
     "tp_problem_poisson_solve", "tp_batch_step", "tp_problem_device_bytes",
@@ -56,6 +57,11 @@ class Params(ctypes.Structure):
 class SolveReport(ctypes.Structure):
     _fields_ = [("cg_iters", ctypes.c_int * 2), ("cg_relres", ctypes.c_double * 2),
                 ("t_ms", ctypes.c_double * 4)]
+
+
+class GmresReport(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("cycles", ctypes.c_int), ("relres", ctypes.c_double),
+                ("precond_cg_iters", ctypes.c_int), ("t_ms", ctypes.c_double), ("omega", ctypes.c_double)]
 
 
 class StepOpts(ctypes.Structure):
@@ -114,6 +120,7 @@ def lib() -> ctypes.CDLL:
         "tp_problem_fractional_apply": [vp, vp, i32, vp],
         "tp_sobolev_apply": [vp, i64, vp, i64, P(Params), vp, i32, vp, vp],
         "tp_problem_sobolev_apply": [vp, vp, i32, vp],
+        "tp_problem_sobolev_solve": [vp, vp, i32, ctypes.c_double, i32, i32, i32, vp, P(GmresReport)],
         "tp_problem_precond_apply": [vp, vp, i32, vp, P(SolveReport)],
         "tp_problem_poisson_solve": [vp, vp, i32, vp, P(SolveReport)],
         "tp_step_opts_default": [P(StepOpts)],
@@ -310,6 +317,22 @@ class Problem:
         Lu = out if out is not None else torch.empty_like(u)
         _check(lib().tp_problem_fractional_apply(self._h, u.data_ptr(), u.shape[1], Lu.data_ptr()))
         return Lu[:, 0] if squeeze else Lu
+
+    def sobolev_solve(self, b, rtol: float = 1e-6, restart: int = 30, maxiter: int = 300, precond: int = 1,
+                      out=None, check: bool = True):
+        """x = A^+ P b by preconditioned GMRES; returns (x, report dict).  precond = 0 uses the
+        paper's preconditioner alone, 1 adds the weighted diagonal of A."""
+        squeeze = b.dim() == 1
+        b = _cols(b, self.nV, "b")
+        x = out if out is not None else torch.empty_like(b)
+        r = GmresReport()
+        st = lib().tp_problem_sobolev_solve(self._h, b.data_ptr(), b.shape[1], rtol, restart, maxiter,
+                                            precond, x.data_ptr(), ctypes.byref(r))
+        if check:
+            _check(st)
+        rep = {"iters": r.iters, "cycles": r.cycles, "relres": r.relres,
+               "precond_cg_iters": r.precond_cg_iters, "t_ms": r.t_ms, "omega": r.omega, "status": st}
+        return (x[:, 0] if squeeze else x), rep
 
     def sobolev_apply(self, u, out=None):
         squeeze = u.dim() == 1
