@@ -232,6 +232,13 @@ typedef struct {
     int    constrain_volume; /* total-volume constraint row (Sec. 7.1.4), default 1      */
     double area_target;      /* NaN selects the area of the mesh at tp_problem_create    */
     double volume_target;    /* NaN selects the volume at tp_problem_create              */
+    int    solver;           /* 0 (default): the direction with A~^{-1} in place of A_3^{-1};
+                                1: A_3^{-1} by GMRES on A = B + B0 (Sec. 5.4, step 3;
+                                tp_problem_sobolev_solve with the diagonal term)           */
+    double solver_rtol;      /* GMRES relative residual, default 1e-4 (solver = 1); with
+                                FP32 pair terms the attainable residual of smooth
+                                right-hand sides (the constraint rows) lies near 1e-6     */
+    int    solver_maxiter;   /* GMRES iterations at most, default 300 (solver = 1)        */
 } tp_step_opts;
 
 TP_API tp_status tp_step_opts_default(tp_step_opts* o);
@@ -244,8 +251,10 @@ typedef struct {
     double tau;              /* accepted step size                                       */
     int    backtracks;
     int    n_constraints;
-    int    cg_iters[2];
-    double cg_relres[2];
+    int    cg_iters[2];      /* the two Poisson solves' iterations; with solver = 1 the
+                                GMRES iterations and the preconditioner's CG iterations  */
+    double cg_relres[2];     /* their relative residuals; with solver = 1 GMRES's true
+                                relative residual and 0                                  */
     double phi_before[2];    /* constraint values Phi(f) (area, volume; unused rows 0)   */
     double phi_trial[2];     /* Phi(f + tau x)                                           */
     double phi_after[2];     /* Phi after the corrective step                            */

@@ -273,6 +273,29 @@ def sobolev_at_vertices(V, F, u, verts, s):
     return Au[np.asarray(verts)]
 
 
+def dense_sobolev_inverse(V, F, s=None, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
+    """R -> A^+ P R with A = B + B0 assembled densely from sobolev_apply on the unit vectors
+    (small meshes only), P the global mean removal and the result of global mean zero: A's
+    null space is the global constants (the low-order term couples connected components)."""
+    V, F = _prep(V, F)
+    if s is None:
+        s = sobolev_s(alpha, beta)
+    n = V.shape[0]
+    A = np.empty((n, n))
+    for c0 in range(0, n, 64):
+        c1 = min(n, c0 + 64)
+        E = np.zeros((n, c1 - c0))
+        E[np.arange(c0, c1), np.arange(c1 - c0)] = 1.0
+        A[:, c0:c1] = sobolev_apply(V, F, E, s)
+    A = 0.5 * (A + A.T) + np.ones((n, n))     # the constants' part of A^+ P R is removed below
+
+    def inverse(R):
+        R = np.asarray(R, dtype=np.float64)
+        Y = np.linalg.solve(A, R - R.mean(0))
+        return Y - Y.mean(0)
+    return inverse
+
+
 def dense_sobolev_matrices(V, F, s):
     """|V| x |V| matrices B and B0 assembled pair by pair from eqs. DiscreteHighOrderTerm and
     DiscreteLowOrderTerm (tiny meshes only), over all ordered pairs S != T.
@@ -455,8 +478,9 @@ ARMIJO_MAX_BACKTRACKS = 30
 
 def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=None,
                  line_search=True, constrain_area=True, constrain_volume=True,
-                 area_target=None, volume_target=None):
-    """One constrained descent step with A~^{-1} in place of A_3^{-1}.
+                 area_target=None, volume_target=None, inverse=None):
+    """One constrained descent step with A~^{-1} in place of A_3^{-1}, or with the map R -> Y
+    given as `inverse` (for instance A_3^{-1} from dense_sobolev_inverse; Sec. 5.4, step 3).
 
     1. g = dE (Sec. 3.1).  2. J = rows of the active constraints: total area (Sec. 7.1.3)
     and total volume (Sec. 7.1.4).  3. Y = A~^{-1} J^T, y_g = A~^{-1} g; Schur matrix
@@ -482,7 +506,7 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     if constrain_volume:
         rows.append(volume_gradient(V, F)); targets.append(V0); fns.append(total_volume)
     R = np.concatenate([g] + rows, axis=1)           # nV x 3(1 + k)
-    Y = precond_apply(V, F, R, sigma, C=C, labels=labels)
+    Y = precond_apply(V, F, R, sigma, C=C, labels=labels) if inverse is None else inverse(R)
     yg = Y[:, 0:3]
     k = len(rows)
     YJ = [Y[:, 3 + 3 * m: 6 + 3 * m] for m in range(k)]

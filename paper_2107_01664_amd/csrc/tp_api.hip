@@ -1844,6 +1844,9 @@ void constraint_values(const StepState& S, const double* hs, double* phi)
 }
 
 // The problems of G share a stream, precision, exponents, sigma and column count.
+tp_status run_sobolev_solve(tp_problem* P, const double* b, int k, double rtol, int m, int maxiter, int precond,
+                            double* x, tp_gmres_report* rep);
+
 tp_status step_group(std::vector<StepState*>& G)
 {
     Batch B;
@@ -1883,9 +1886,23 @@ tp_status step_group(std::vector<StepState*>& G)
             col += 3;
         }
     }
-    // 3. Y = A~^{-1} R (shared all-pairs and CG launches)
+    // 3. Y = A~^{-1} R (shared all-pairs and CG launches), or with solver = 1 Y = A^+ R by
+    //    GMRES on the true operator, one problem at a time (Sec. 5.4, step 3)
     tm.mark(1);
-    {
+    const bool gmres = G[0]->o.solver == 1;
+    std::vector<tp_gmres_report> grep(G.size());
+    std::vector<tp_status> gst(G.size(), TP_OK);
+    if (gmres) {
+        for (size_t q = 0; q < G.size(); ++q) {
+            StepState* S = G[q];
+            gst[q] = run_sobolev_solve(S->P, S->P->R.p, ncol, S->o.solver_rtol, std::min(50, 1024 / ncol - 1),
+                                       S->o.solver_maxiter, 1, S->P->Y.p, &grep[q]);
+            if (gst[q] == TP_E_DEVICE) return gst[q];
+        }
+        tm.mark(2);
+        tm.mark(3);
+        tm.mark(4);
+    } else {
         std::vector<const double*> Rp;
         std::vector<double*> Yp;
         for (tp_problem* P : B) {
@@ -1914,10 +1931,20 @@ tp_status step_group(std::vector<StepState*>& G)
         const double* h = P->hs.p;
         if ((S->st = flag_status(P)) != TP_OK) continue;
         S->R.cg_iters[0] = 0;
-        const tp_status c1 = cg_result(P, ncol, 0, &S->R.cg_iters[0], &S->R.cg_relres[0]);
-        const tp_status c2 = cg_result(P, ncol, 1, &S->R.cg_iters[1], &S->R.cg_relres[1]);
-        if (c1 != TP_OK) S->st = c1;
-        else if (c2 != TP_OK) S->st = c2;
+        if (gmres) {
+            // GMRES iterations and true relative residual; CG iterations of its preconditioner
+            const size_t q = (size_t)(std::find(G.begin(), G.end(), S) - G.begin());
+            S->R.cg_iters[0] = grep[q].iters;
+            S->R.cg_relres[0] = grep[q].relres;
+            S->R.cg_iters[1] = grep[q].precond_cg_iters;
+            S->R.cg_relres[1] = 0.0;
+            if (gst[q] != TP_OK) S->st = gst[q];
+        } else {
+            const tp_status c1 = cg_result(P, ncol, 0, &S->R.cg_iters[0], &S->R.cg_relres[0]);
+            const tp_status c2 = cg_result(P, ncol, 1, &S->R.cg_iters[1], &S->R.cg_relres[1]);
+            if (c1 != TP_OK) S->st = c1;
+            else if (c2 != TP_OK) S->st = c2;
+        }
         S->E0 = gradient_energy(P, h[kSlotE]);
         if (!finite(S->E0)) {
             S->st = fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
@@ -2120,6 +2147,11 @@ tp_status run_step_batch(tp_problem* const* probs, int n, const tp_step_opts* op
             T.st = fail(TP_E_INVALID_ARGUMENT, "max_backtracks must be >= 0");
             continue;
         }
+        if ((T.o.solver != 0 && T.o.solver != 1) ||
+            (T.o.solver == 1 && (!(T.o.solver_rtol > 0.0) || T.o.solver_maxiter < 1))) {
+            T.st = fail(TP_E_INVALID_ARGUMENT, "solver must be 0 or 1 (then solver_rtol > 0, solver_maxiter >= 1)");
+            continue;
+        }
         tp_problem* P = T.P;
         tp_status st = ensure_initial_measures(P);
         if (st == TP_OK) st = ensure_geometry(P);
@@ -2144,7 +2176,8 @@ tp_status run_step_batch(tp_problem* const* probs, int n, const tp_step_opts* op
             const tp_problem* b = S[q].P;
             if (a->prm.precision == b->prm.precision && a->prm.alpha == b->prm.alpha &&
                 a->prm.beta == b->prm.beta && a->sigma == b->sigma && S[m].ncol == S[q].ncol &&
-                a->prm.theta == b->prm.theta && a->prm.leaf_size == b->prm.leaf_size) {
+                a->prm.theta == b->prm.theta && a->prm.leaf_size == b->prm.leaf_size &&
+                S[m].o.solver == S[q].o.solver) {
                 G.push_back(&S[q]);
                 done[q] = true;
             }
@@ -2270,6 +2303,9 @@ tp_status tp_step_opts_default(tp_step_opts* o)
     o->constrain_volume = 1;
     o->area_target = NAN;
     o->volume_target = NAN;
+    o->solver = 0;
+    o->solver_rtol = 1e-4;
+    o->solver_maxiter = 300;
     return TP_OK;
 }
 

@@ -68,7 +68,8 @@ class StepOpts(ctypes.Structure):
     _fields_ = [("tau0", ctypes.c_double), ("line_search", ctypes.c_int), ("armijo_c", ctypes.c_double),
                 ("shrink", ctypes.c_double), ("max_backtracks", ctypes.c_int),
                 ("constrain_area", ctypes.c_int), ("constrain_volume", ctypes.c_int),
-                ("area_target", ctypes.c_double), ("volume_target", ctypes.c_double)]
+                ("area_target", ctypes.c_double), ("volume_target", ctypes.c_double),
+                ("solver", ctypes.c_int), ("solver_rtol", ctypes.c_double), ("solver_maxiter", ctypes.c_int)]
 
 
 class StepReport(ctypes.Structure):

@@ -643,3 +643,25 @@ def test_sobolev_solve_cap_and_errors(tp, meshes):
             assert st == 1, (args, st)
         st = L.tp_problem_sobolev_solve(P._h, b.data_ptr(), 2, 1e-6, 10, 10, 2, x.data_ptr(), ctypes.byref(r))
         assert st == 1, st
+
+
+@pytest.mark.parametrize("prec,rtol,tol", [(2, 1e-10, 1e-6), (0, 1e-5, 1e-3), (0, 1e-4, 1e-2)])
+def test_step_true_operator(tp, meshes, prec, rtol, tol):
+    """A descent step whose direction uses A_3^{-1} by GMRES (solver = 1) against the
+    oracle's step with the dense A^+ (fixed tau): direction, new vertices, constraints."""
+    m = meshes["small_sphere"]
+    print(f"[parity] step with GMRES on A, precision={prec}", flush=True)
+    tau = 2e-3
+    ref = O.precond_step(m.V, m.F, tau=tau, line_search=False, inverse=O.dense_sobolev_inverse(m.V, m.F, S_SOB))
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32), tp.default_params(precision=prec)) as P:
+        d = torch.empty((m.nV, 3), dtype=torch.float64, device="cuda")
+        rep = P.step(tp.step_opts(tau0=tau, line_search=0, solver=1, solver_rtol=rtol, solver_maxiter=400),
+                     direction=d)
+        Vn = P.vertices().cpu().numpy()
+    x = d.cpu().numpy()
+    print("  gmres iters", rep.cg_iters[0], "relres", rep.cg_relres[0], "precond cg", rep.cg_iters[1],
+          "direction error", rel(x, ref.direction), flush=True)
+    assert rel(x, ref.direction) <= tol, rel(x, ref.direction)
+    assert rel(Vn - m.V, ref.V - m.V) <= tol
+    assert rep.slope < 0
+    assert np.abs(np.asarray(rep.phi_after)).max() <= 10 * np.abs(ref.phi_after).max() + 1e-12

@@ -493,3 +493,26 @@ def test_preconditioner_spectrum_and_diagonal_term():
     (p2, d2), (p3, d3) = spreads
     assert p3 > 2.5 * p2, spreads
     assert d2 < 10.0 and d3 < 10.0, spreads
+
+
+def test_dense_sobolev_inverse_and_true_operator_step():
+    """The oracle's A^+ P solves A Y = P R with global mean zero; the step built on it solves
+    the saddle-point system of Sec. 3.3 with the true operator: J x = 0 and
+    A x + g lies in the span of the constraint rows and the constants."""
+    m = mg.add_noise(mg.icosphere(1), 0.03, 4)
+    s = 5.0 / 3.0
+    inv = O.dense_sobolev_inverse(m.V, m.F, s)
+    R = RNG.standard_normal((m.nV, 3))
+    Y = inv(R)
+    assert rel(O.sobolev_apply(m.V, m.F, Y, s), R - R.mean(0)) < 1e-10
+    assert np.abs(Y.mean(0)).max() < 1e-12 * np.abs(Y).max()
+    res = O.precond_step(m.V, m.F, tau=1e-3, line_search=False, inverse=inv)
+    x = res.direction
+    _, g = O.gradient(m.V, m.F)
+    JA, JV = O.area_gradient(m.V, m.F), O.volume_gradient(m.V, m.F)
+    assert abs(np.vdot(JA, x)) < 1e-10 * np.linalg.norm(JA) * np.linalg.norm(x)
+    assert abs(np.vdot(JV, x)) < 1e-10 * np.linalg.norm(JV) * np.linalg.norm(x)
+    lhs = (O.sobolev_apply(m.V, m.F, x, s) + g).ravel()
+    basis = np.stack([JA.ravel(), JV.ravel()] + [np.kron(np.ones(m.nV), np.eye(3)[c]) for c in range(3)], 1)
+    coef, *_ = np.linalg.lstsq(basis, lhs, rcond=None)
+    assert np.linalg.norm(basis @ coef - lhs) < 1e-9 * np.linalg.norm(g)
