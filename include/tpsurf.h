@@ -207,6 +207,9 @@ typedef struct {
  * b, x_out: device, nV x k row-major double; b is not modified.  Requires rtol > 0,
  * 1 <= restart <= 100, (restart + 1) k <= 1024, maxiter >= 1, precond 0 or 1
  * (TP_E_INVALID_ARGUMENT).
+ * The preconditioner's Poisson solves run to relative residual 1e-3 (or cg_rtol if looser):
+ * the flexible form needs no more, since the residual is formed with the directions the
+ * preconditioner returned.
  * Device memory: 2 (restart + 1) nV k doubles of Krylov vectors, held by the problem. */
 TP_API tp_status tp_problem_sobolev_solve(tp_problem* prob, const double* b, int k, double rtol, int restart,
                                           int maxiter, int precond, double* x_out, tp_gmres_report* report);

@@ -1359,6 +1359,20 @@ tp_status run_sobolev(tp_problem* P, const double* u, int ldu, int k, double* Au
 // omega = w^T A~^{-1} w / w^T v with w = A v, v the coordinate functions (averaged over
 // the three).  The diagonal is taken without the pairs of faces that share the vertex.
 constexpr int kGmCoarseMax = 16;
+//
+// The preconditioner's Poisson solves run to kGmInnerRtol (or the problem's cg_rtol if
+// looser): the flexible form forms the residual with the directions the preconditioner
+// actually returned, so their accuracy changes the rate of convergence, not the solution's
+// (on torus40k to 1e-6: 18 iterations with inner tolerances from 1e-10 to 1e-3, and 37 %
+// less time at 1e-3).
+constexpr double kGmInnerRtol = 1e-3;
+
+struct CgRtolGuard {   // the CG tolerance of a problem, restored on every exit path
+    tp_problem* P;
+    double saved;
+    CgRtolGuard(tp_problem* P_, double r) : P(P_), saved(P_->prm.cg_rtol) { P->prm.cg_rtol = std::max(saved, r); }
+    ~CgRtolGuard() { P->prm.cg_rtol = saved; }
+};
 
 tp_status run_precond(tp_problem* P, const double* b, int k, double* x, tp_solve_report* rep);
 
@@ -1390,6 +1404,7 @@ tp_status run_sobolev_solve(tp_problem* P, const double* b, int k, double rtol, 
     double* sm = P->gm_small.p;
     EventTimer tm(s);
     tm.mark(0);
+    CgRtolGuard inner(P, kGmInnerRtol);
     std::vector<double> Gchol;   // Cholesky factor (lower, row-major) of G + tr(G)/nc e e^T
     if (coarse) {
         TP_TRY(P->gm_lab0.ensure((size_t)n, s));
