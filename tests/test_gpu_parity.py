@@ -665,3 +665,47 @@ def test_step_true_operator(tp, meshes, prec, rtol, tol):
     assert rel(Vn - m.V, ref.V - m.V) <= tol
     assert rep.slope < 0
     assert np.abs(np.asarray(rep.phi_after)).max() <= 10 * np.abs(ref.phi_after).max() + 1e-12
+
+
+def test_sobolev_solve_many_components(tp):
+    """17 separate noisy icosahedra (more components than the coarse solve takes): the solve
+    is the Galerkin one on the functions of mean zero per component, P A x = P b with P the
+    per-component mean removal; checked against the dense oracle solution of that system."""
+    base = mg.add_noise(mg.icosahedron(), 0.05, 5)
+    nc = 17
+    offs = [np.array([3.0 * (q % 5), 3.0 * (q // 5), 0.4 * q]) for q in range(nc)]
+    V = np.concatenate([base.V + o for o in offs])
+    F = np.concatenate([base.F + q * base.nV for q in range(nc)]).astype(np.int32)
+    n = V.shape[0]
+    print("[parity] sobolev solve with 17 components", flush=True)
+    b = mg.random_columns(n, 2, 17)
+    with tp.Problem(dev(V), dev(F, torch.int32), tp.default_params(precision=2)) as P:
+        x, rep = P.sobolev_solve(dev(b), rtol=1e-10, restart=40, maxiter=400)
+    x = x.cpu().numpy()
+    print("  report", rep, flush=True)
+    _, labels = O.components(F, n)
+    Q = np.stack([(labels == l).astype(float) for l in range(nc)], 1)
+    Pc = np.eye(n) - Q @ np.diag(1.0 / Q.sum(0)) @ Q.T
+    A = _dense_sobolev(mg.Mesh(V, F))
+    xs = np.linalg.solve(Pc @ A @ Pc + Q @ Q.T, Pc @ b)
+    assert np.abs(Q.T @ x).max() <= 1e-10 * np.abs(x).max()
+    assert rel(x, xs) <= 1e-7, rel(x, xs)
+
+
+def test_sobolev_solve_multi_launch_preconditioner(tp, sphere41k):
+    """41K-vertex sphere: the preconditioner's Poisson solves take the multi-launch form
+    (more blocks than one cooperative launch holds); GMRES to 1e-4 on dE, A x against the
+    oracle at sampled vertices."""
+    m = sphere41k
+    print("[parity] sobolev solve sphere41k", flush=True)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        _, dE = P.gradient()
+        x, rep = P.sobolev_solve(dE, rtol=1e-4, restart=50, maxiter=200)
+        b = dE.cpu().numpy()
+    x = x.cpu().numpy()
+    print("  report", rep, flush=True)
+    assert rep["relres"] <= 1e-4 and rep["iters"] <= 40, rep
+    Pb = b - b.mean(0)
+    verts = np.random.default_rng(3).choice(m.nV, 8, replace=False)
+    Ax = O.sobolev_at_vertices(m.V, m.F, x, verts, S_SOB)
+    assert np.linalg.norm(Ax - Pb[verts]) <= 2e-4 * np.linalg.norm(Pb), np.linalg.norm(Ax - Pb[verts])
