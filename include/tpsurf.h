@@ -242,6 +242,13 @@ typedef struct {
                                 FP32 pair terms the attainable residual of smooth
                                 right-hand sides (the constraint rows) lies near 1e-6     */
     int    solver_maxiter;   /* GMRES iterations at most, default 300 (solver = 1)        */
+    double area_penalty;     /* w_A >= 0 of the potential w_A (A / A_0 - 1)^2 (Sec. 7.2),
+                                A_0 = area_target; default 0                              */
+    double volume_penalty;   /* w_V >= 0 of w_V (V / V_0 - 1)^2, V_0 = volume_target;
+                                default 0.  With either weight > 0 the step minimises
+                                the tangent-point energy plus the potentials: their
+                                gradients join dE, the line search and E / E_new of the
+                                report include them                                       */
 } tp_step_opts;
 
 TP_API tp_status tp_step_opts_default(tp_step_opts* o);

@@ -478,7 +478,8 @@ ARMIJO_MAX_BACKTRACKS = 30
 
 def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=None,
                  line_search=True, constrain_area=True, constrain_volume=True,
-                 area_target=None, volume_target=None, inverse=None):
+                 area_target=None, volume_target=None, inverse=None, area_penalty=0.0,
+                 volume_penalty=0.0):
     """One constrained descent step with A~^{-1} in place of A_3^{-1}, or with the map R -> Y
     given as `inverse` (for instance A_3^{-1} from dense_sobolev_inverse; Sec. 5.4, step 3).
 
@@ -490,7 +491,10 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     4. Armijo backtracking from tau0 (constants c = 1e-4, shrink 1/2, at most 30 halvings;
     the paper names the rule but not the constants).  tau0 defaults to the step whose
     largest vertex move is half the mean edge length.  With line_search=False, tau = tau0.
-    5. Corrective step h = -Y S^{-1} Phi(f + tau x) (Sec. 5.4.1), added to f + tau x."""
+    5. Corrective step h = -Y S^{-1} Phi(f + tau x) (Sec. 5.4.1), added to f + tau x.
+    With area_penalty / volume_penalty > 0 the objective is E plus the potentials of Sec. 7.2
+    (penalty_terms): their gradients join g and the line search, and E of the result is the
+    total."""
     V, F = _prep(V, F)
     nV = V.shape[0]
     if sigma is None:
@@ -500,6 +504,15 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     E0, g = gradient(V, F, alpha, beta)
     A0 = total_area(V, F) if area_target is None else area_target
     V0 = total_volume(V, F) if volume_target is None else volume_target
+    if area_penalty > 0.0 or volume_penalty > 0.0:
+        p0, gp = penalty_terms(V, F, A0, V0, area_penalty, volume_penalty)
+        E0, g = E0 + p0, g + gp
+
+    def objective(Vx):
+        e = energy(Vx, F, alpha, beta)
+        if area_penalty > 0.0 or volume_penalty > 0.0:
+            e += penalty_terms(Vx, F, A0, V0, area_penalty, volume_penalty)[0]
+        return e
     rows, targets, fns = [], [], []
     if constrain_area:
         rows.append(area_gradient(V, F)); targets.append(A0); fns.append(total_area)
@@ -527,7 +540,7 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     t = tau0
     bt = 0
     if line_search:
-        while energy(V + t * x, F, alpha, beta) > E0 + ARMIJO_C * t * slope and bt < ARMIJO_MAX_BACKTRACKS:
+        while objective(V + t * x) > E0 + ARMIJO_C * t * slope and bt < ARMIJO_MAX_BACKTRACKS:
             t *= ARMIJO_SHRINK
             bt += 1
     Vt = V + t * x
@@ -542,6 +555,16 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
         phi = phi_after = phi_before
     return StepResult(V=Vn, E=E0, grad_norm=float(np.linalg.norm(g)), tau=t, backtracks=bt,
                       direction=x, phi_before=phi_before, phi_after=phi_after, phi_trial=phi, schur=S)
+
+
+def penalty_terms(V, F, A0, V0, area_weight, volume_weight):
+    """Total area and volume potentials of Sec. 7.2, w_A (A/A0 - 1)^2 + w_V (V/V0 - 1)^2, and
+    their gradient with respect to the vertex positions (nV x 3)."""
+    A, Vol = total_area(V, F), total_volume(V, F)
+    e = area_weight * (A / A0 - 1.0) ** 2 + volume_weight * (Vol / V0 - 1.0) ** 2
+    g = (2.0 * area_weight * (A / A0 - 1.0) / A0) * area_gradient(V, F) + \
+        (2.0 * volume_weight * (Vol / V0 - 1.0) / V0) * volume_gradient(V, F)
+    return e, g
 
 
 def _mean_edge_length(V, F) -> float:

@@ -1838,6 +1838,16 @@ struct StepState {
     tp_status st = TP_OK;
     double* dir_out = nullptr;
     bool alive() const { return st == TP_OK || st == TP_E_NOT_CONVERGED; }
+    bool penalized() const { return o.area_penalty > 0.0 || o.volume_penalty > 0.0; }
+    // w_A (A / A0 - 1)^2 + w_V (V / V0 - 1)^2 (Sec. 7.2), A and V the total area and volume
+    double penalty(double area, double vol) const
+    {
+        double e = 0.0;
+        if (o.area_penalty > 0.0) e += o.area_penalty * (area / A0 - 1.0) * (area / A0 - 1.0);
+        if (o.volume_penalty > 0.0) e += o.volume_penalty * (vol / V0 - 1.0) * (vol / V0 - 1.0);
+        return e;
+    }
+    double pen0 = 0.0;   // the penalty at the start of the step
 };
 
 // Area and six times the signed volume at Vsrc (the face data must describe Vsrc).
@@ -1884,6 +1894,38 @@ tp_status step_group(std::vector<StepState*>& G)
         std::vector<double*> gp;
         for (tp_problem* P : B) gp.push_back(P->gbuf.p);
         TP_TRY(enqueue_gradient(B, gp.data(), kSlotE));
+    }
+    // 1b. penalty potentials (Sec. 7.2): their gradients are added to g,
+    //     2 w_A (A / A0 - 1) / A0 dA + 2 w_V (V / V0 - 1) / V0 dV
+    {
+        Batch BP;
+        for (StepState* S : G)
+            if (S->penalized()) {
+                TP_TRY(enqueue_area_volume(S->P, S->P->V.p));   // face data describes V
+                BP.push_back(S->P);
+            }
+        if (!BP.empty()) {
+            TP_TRY(enqueue_fetch(BP));
+            TP_TRY(sync_batch(BP));
+        }
+        for (StepState* S : G) {
+            if (!S->penalized()) continue;
+            tp_problem* P = S->P;
+            const int64_t n = P->nV;
+            const double area = P->hs.p[kSlotArea], vol = P->hs.p[kSlotVol6] / 6.0;
+            S->pen0 = S->penalty(area, vol);
+            const int c0 = 0;
+            if (S->o.area_penalty > 0.0) {
+                const double cA = 2.0 * S->o.area_penalty * (area / S->A0 - 1.0) / S->A0;
+                TP_HIP(launch_spmm(n, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->V.p, 3, 3, P->Y.p, 3, s));
+                TP_HIP(launch_axpy_block3(n, P->gbuf.p, 3, 1.0, P->Y.p, 3, 1, &cA, &c0, P->gbuf.p, 3, s));
+            }
+            if (S->o.volume_penalty > 0.0) {
+                const double cV = 2.0 * S->o.volume_penalty * (vol / S->V0 - 1.0) / S->V0;
+                TP_HIP(launch_volume_gradient(P->V.p, P->F.p, n, P->vf_off.p, P->vf_idx.p, P->Vt.p, 3, 0, s));
+                TP_HIP(launch_axpy_block3(n, P->gbuf.p, 3, 1.0, P->Vt.p, 3, 1, &cV, &c0, P->gbuf.p, 3, s));
+            }
+        }
     }
     // 2. right-hand sides: g, area gradient C f (twice the mean curvature normal), volume
     //    gradient
@@ -1960,7 +2002,7 @@ tp_status step_group(std::vector<StepState*>& G)
             if (c1 != TP_OK) S->st = c1;
             else if (c2 != TP_OK) S->st = c2;
         }
-        S->E0 = gradient_energy(P, h[kSlotE]);
+        S->E0 = gradient_energy(P, h[kSlotE]) + S->pen0;
         if (!finite(S->E0)) {
             S->st = fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
             continue;
@@ -2036,6 +2078,7 @@ tp_status step_group(std::vector<StepState*>& G)
             P->fd_V = P->Vt.p;
             ++P->geom_ver;
             P->geom_valid = false;
+            if (S->penalized()) TP_TRY(enqueue_area_volume(P, P->Vt.p));
             BS.push_back(P);
         }
         TP_TRY(enqueue_energy(BS, kSlotE));
@@ -2049,7 +2092,7 @@ tp_status step_group(std::vector<StepState*>& G)
                 S->st = gs;
                 continue;
             }
-            const double Et = P->hs.p[kSlotE];
+            const double Et = P->hs.p[kSlotE] + (S->penalized() ? S->penalty(P->hs.p[kSlotArea], P->hs.p[kSlotVol6] / 6.0) : 0.0);
             const bool valid = gs == TP_OK && finite(Et);
             const bool ok = valid && (!S->o.line_search || Et <= S->E0 + S->o.armijo_c * S->tau * S->R.slope);
             if (ok || !S->o.line_search) {
@@ -2122,7 +2165,7 @@ tp_status step_group(std::vector<StepState*>& G)
         }
         P->geom_valid = true;
         constraint_values(*S, P->hs.p, S->R.phi_after);
-        S->R.E_new = P->hs.p[kSlotE];
+        S->R.E_new = P->hs.p[kSlotE] + S->penalty(P->hs.p[kSlotArea], P->hs.p[kSlotVol6] / 6.0);
     }
     // timings of the group (shared by its problems)
     const double t[8] = {tm.ms(0, 1), tm.ms(1, 2), tm.ms(1, 4), tm.ms(4, 5),
@@ -2160,6 +2203,10 @@ tp_status run_step_batch(tp_problem* const* probs, int n, const tp_step_opts* op
         }
         if (T.o.max_backtracks < 0) {
             T.st = fail(TP_E_INVALID_ARGUMENT, "max_backtracks must be >= 0");
+            continue;
+        }
+        if (!(T.o.area_penalty >= 0.0) || !(T.o.volume_penalty >= 0.0)) {
+            T.st = fail(TP_E_INVALID_ARGUMENT, "penalty weights must be >= 0");
             continue;
         }
         if ((T.o.solver != 0 && T.o.solver != 1) ||
@@ -2321,6 +2368,8 @@ tp_status tp_step_opts_default(tp_step_opts* o)
     o->solver = 0;
     o->solver_rtol = 1e-4;
     o->solver_maxiter = 300;
+    o->area_penalty = 0.0;
+    o->volume_penalty = 0.0;
     return TP_OK;
 }
 

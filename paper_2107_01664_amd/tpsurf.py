@@ -69,7 +69,8 @@ class StepOpts(ctypes.Structure):
                 ("shrink", ctypes.c_double), ("max_backtracks", ctypes.c_int),
                 ("constrain_area", ctypes.c_int), ("constrain_volume", ctypes.c_int),
                 ("area_target", ctypes.c_double), ("volume_target", ctypes.c_double),
-                ("solver", ctypes.c_int), ("solver_rtol", ctypes.c_double), ("solver_maxiter", ctypes.c_int)]
+                ("solver", ctypes.c_int), ("solver_rtol", ctypes.c_double), ("solver_maxiter", ctypes.c_int),
+                ("area_penalty", ctypes.c_double), ("volume_penalty", ctypes.c_double)]
 
 
 class StepReport(ctypes.Structure):

@@ -709,3 +709,28 @@ def test_sobolev_solve_multi_launch_preconditioner(tp, sphere41k):
     verts = np.random.default_rng(3).choice(m.nV, 8, replace=False)
     Ax = O.sobolev_at_vertices(m.V, m.F, x, verts, S_SOB)
     assert np.linalg.norm(Ax - Pb[verts]) <= 2e-4 * np.linalg.norm(Pb), np.linalg.norm(Ax - Pb[verts])
+
+
+def test_step_penalties(tp, meshes):
+    """Area and volume potentials in place of the hard constraints (targets 10 % off the
+    current values, so the potentials' gradients matter): the step at fixed tau against the
+    oracle's, and the reported total objective."""
+    m = meshes["small_sphere"]
+    print("[parity] step with area and volume potentials", flush=True)
+    A0, V0 = 0.9 * O.total_area(m.V, m.F), 1.1 * O.total_volume(m.V, m.F)
+    tau = 2e-3
+    ref = O.precond_step(m.V, m.F, tau=tau, line_search=False, constrain_area=False, constrain_volume=False,
+                         area_target=A0, volume_target=V0, area_penalty=5.0, volume_penalty=5.0)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        d = torch.empty((m.nV, 3), dtype=torch.float64, device="cuda")
+        rep = P.step(tp.step_opts(tau0=tau, line_search=0, constrain_area=0, constrain_volume=0, area_target=A0,
+                                  volume_target=V0, area_penalty=5.0, volume_penalty=5.0), direction=d)
+        Vn = P.vertices().cpu().numpy()
+    x = d.cpu().numpy()
+    print("  direction error", rel(x, ref.direction), "E", rep.E, ref.E, flush=True)
+    assert rel(x, ref.direction) <= 1e-4, rel(x, ref.direction)
+    assert rel(Vn - m.V, ref.V - m.V) <= 1e-4
+    assert abs(rep.E - ref.E) <= TOL32 * ref.E
+    E_new = O.energy(Vn, m.F) + O.penalty_terms(Vn, m.F, A0, V0, 5.0, 5.0)[0]
+    assert abs(rep.E_new - E_new) <= TOL32 * E_new
+    assert rep.slope < 0

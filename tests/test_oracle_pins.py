@@ -516,3 +516,24 @@ def test_dense_sobolev_inverse_and_true_operator_step():
     basis = np.stack([JA.ravel(), JV.ravel()] + [np.kron(np.ones(m.nV), np.eye(3)[c]) for c in range(3)], 1)
     coef, *_ = np.linalg.lstsq(basis, lhs, rcond=None)
     assert np.linalg.norm(basis @ coef - lhs) < 1e-9 * np.linalg.norm(g)
+
+
+def test_penalty_potentials(noisy2):
+    """The area and volume potentials of Sec. 7.2: gradient against central differences; a
+    step on them alone (no hard constraints) descends the total objective."""
+    V, F = noisy2.V, noisy2.F
+    A0, V0 = 0.9 * O.total_area(V, F), 1.1 * O.total_volume(V, F)
+    e, g = O.penalty_terms(V, F, A0, V0, 3.0, 2.0)
+    rng = np.random.default_rng(8)
+    for _ in range(3):
+        d = rng.standard_normal(V.shape)
+        h = 1e-6
+        fd = (O.penalty_terms(V + h * d, F, A0, V0, 3.0, 2.0)[0] - O.penalty_terms(V - h * d, F, A0, V0, 3.0, 2.0)[0]) / (2 * h)
+        assert abs(fd - np.vdot(g, d)) <= 1e-6 * (abs(fd) + 1e-12), (fd, np.vdot(g, d))
+    res = O.precond_step(V, F, constrain_area=False, constrain_volume=False, area_target=A0,
+                         volume_target=V0, area_penalty=3.0, volume_penalty=2.0)
+    E_tp = O.energy(V, F)
+    assert abs(res.E - (E_tp + e)) <= 1e-12 * res.E
+    Vn = res.V
+    E_new = O.energy(Vn, F) + O.penalty_terms(Vn, F, A0, V0, 3.0, 2.0)[0]
+    assert E_new < res.E
