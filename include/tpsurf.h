@@ -174,6 +174,20 @@ TP_API tp_status tp_problem_gradient(tp_problem* prob, double* E_out, double* dE
 TP_API tp_status tp_problem_fractional_apply(tp_problem* prob, const double* u, int k, double* Lu_out);
 TP_API tp_status tp_problem_sobolev_apply(tp_problem* prob, const double* u, int k, double* Au_out);
 
+/* Static obstacle (Sec. 7.2): a fixed mesh (Vo: nVo x 3 double, Fo: nFo x 3 int32, device,
+ * copied at the call) that repels the surface with the potential
+ *   E_obs = sum_T a_T sum_{S in obstacle} a_O(S) |X_O(S) - X_T|^-p
+ * (the obstacle potential of the paper evaluated at the barycenter of every face T of the
+ * surface and integrated over T; FP64 direct sums, not Barnes-Hut).  With weight > 0 every
+ * later descent step of this problem minimises E + weight E_obs (gradient, line search and
+ * the report's energies).  nFo = 0 or weight = 0 removes the obstacle.  Errors:
+ * TP_E_INVALID_ARGUMENT for bad sizes, indices, p <= 0 or weight < 0. */
+TP_API tp_status tp_problem_set_obstacle(tp_problem* prob, const double* Vo, int64_t nVo, const int32_t* Fo,
+                                         int64_t nFo, double p, double weight);
+/* E_out = E_obs (unweighted) at the current vertices; dE_out (device nV x 3, or NULL) its
+ * differential with respect to the surface's vertex positions. */
+TP_API tp_status tp_problem_obstacle_energy(tp_problem* prob, double* E_out, double* dE_out);
+
 /* Report of one GMRES solve with A (tp_problem_sobolev_solve). */
 typedef struct {
     int    iters;             /* GMRES iterations (one preconditioner and one A product each) */

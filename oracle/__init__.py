@@ -54,6 +54,8 @@ def lib():
         L.tpo_sobolev_gather.argtypes = [_dp, _ip, i64, i64, _dp, ctypes.c_int, _dp]
         L.tpo_sobolev_apply.argtypes = [_dp, i64, _ip, i64, d, _dp, ctypes.c_int, _dp]
         L.tpo_sobolev_apply.restype = ctypes.c_int
+        L.tpo_obstacle.argtypes = [_dp, i64, _ip, i64, _dp, _ip, i64, d, _dp]
+        L.tpo_obstacle.restype = d
         L.tpo_bh_frozen.argtypes = [_dp, _dp, i64, _ip, i64, d, d, d, ctypes.c_int, _dp, _lp]
         L.tpo_bh_frozen.restype = d
         L.tpo_bh_order.argtypes = [_dp, _ip, i64, ctypes.c_int, _lp]
@@ -479,7 +481,7 @@ ARMIJO_MAX_BACKTRACKS = 30
 def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=None,
                  line_search=True, constrain_area=True, constrain_volume=True,
                  area_target=None, volume_target=None, inverse=None, area_penalty=0.0,
-                 volume_penalty=0.0):
+                 volume_penalty=0.0, obstacle_mesh=None, obstacle_p=6.0, obstacle_weight=0.0):
     """One constrained descent step with A~^{-1} in place of A_3^{-1}, or with the map R -> Y
     given as `inverse` (for instance A_3^{-1} from dense_sobolev_inverse; Sec. 5.4, step 3).
 
@@ -494,7 +496,8 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     5. Corrective step h = -Y S^{-1} Phi(f + tau x) (Sec. 5.4.1), added to f + tau x.
     With area_penalty / volume_penalty > 0 the objective is E plus the potentials of Sec. 7.2
     (penalty_terms): their gradients join g and the line search, and E of the result is the
-    total."""
+    total.  obstacle_mesh = (Vo, Fo) with obstacle_weight > 0 adds weight x the obstacle
+    potential (obstacle) to the objective in the same way."""
     V, F = _prep(V, F)
     nV = V.shape[0]
     if sigma is None:
@@ -507,11 +510,17 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     if area_penalty > 0.0 or volume_penalty > 0.0:
         p0, gp = penalty_terms(V, F, A0, V0, area_penalty, volume_penalty)
         E0, g = E0 + p0, g + gp
+    use_obs = obstacle_mesh is not None and obstacle_weight > 0.0
+    if use_obs:
+        eo, go = obstacle(V, F, obstacle_mesh[0], obstacle_mesh[1], obstacle_p)
+        E0, g = E0 + obstacle_weight * eo, g + obstacle_weight * go
 
     def objective(Vx):
         e = energy(Vx, F, alpha, beta)
         if area_penalty > 0.0 or volume_penalty > 0.0:
             e += penalty_terms(Vx, F, A0, V0, area_penalty, volume_penalty)[0]
+        if use_obs:
+            e += obstacle_weight * obstacle(Vx, F, obstacle_mesh[0], obstacle_mesh[1], obstacle_p, False)[0]
         return e
     rows, targets, fns = [], [], []
     if constrain_area:
@@ -555,6 +564,17 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
         phi = phi_after = phi_before
     return StepResult(V=Vn, E=E0, grad_norm=float(np.linalg.norm(g)), tau=t, backtracks=bt,
                       direction=x, phi_before=phi_before, phi_after=phi_after, phi_trial=phi, schur=S)
+
+
+def obstacle(V, F, Vo, Fo, p=6.0, with_grad=True):
+    """Static obstacle potential of Sec. 7.2 at the surface's face barycenters, integrated over
+    the faces, and its differential with respect to the surface vertices (tpo_obstacle)."""
+    V, F = _prep(V, F)
+    Vo, Fo = _prep(Vo, Fo)
+    dE = np.empty_like(V) if with_grad else None
+    E = lib().tpo_obstacle(_d(V), V.shape[0], _i(F), F.shape[0], _d(Vo), _i(Fo), Fo.shape[0], p,
+                           _d(dE) if with_grad else None)
+    return float(E), dE
 
 
 def penalty_terms(V, F, A0, V0, area_weight, volume_weight):

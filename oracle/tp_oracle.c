@@ -487,6 +487,51 @@ EXPORT int tpo_sobolev_apply(const double* V, int64_t nV, const int32_t* F, int6
 }
 
 /* ------------------------------------------------------------------------- */
+/* Static obstacle potential (Sec. 7.2): the obstacle's potential sum_S a_O(S) |X_O(S) - x|^-p
+ * evaluated at the barycenter of every surface face T and integrated over T:
+ *   E_obs = sum_T a_T phi(T),  phi(T) = sum_S a_O(S) |X_O(S) - X_T|^-p.
+ * Its differential with respect to the surface vertices, by the chain rule through X_T
+ * (d X_T / d f_i = I/3 for the corners) and a_T (d a_T / d f_i = N_T x (f_k - f_j) / 2 for
+ * the corners i, j, k of T in cyclic order).  dE (nV x 3) may be NULL. */
+EXPORT double tpo_obstacle(const double* V, int64_t nV, const int32_t* F, int64_t nF, const double* Vo,
+                           const int32_t* Fo, int64_t nFo, double p, double* dE)
+{
+    double* XO = malloc(sizeof(double) * 3 * nFo);
+    double* AO = malloc(sizeof(double) * nFo);
+    for (int64_t S = 0; S < nFo; ++S) {
+        double N[3], c[3];
+        face_quantities(Vo, Fo, S, XO + 3 * S, N, AO + S, c);
+    }
+    if (dE) memset(dE, 0, sizeof(double) * 3 * nV);
+    double E = 0.0;
+    for (int64_t T = 0; T < nF; ++T) {
+        double X[3], N[3], a, c[3];
+        face_quantities(V, F, T, X, N, &a, c);
+        double phi = 0.0, g[3] = {0.0, 0.0, 0.0};
+        for (int64_t S = 0; S < nFo; ++S) {
+            double d[3] = {X[0] - XO[3 * S], X[1] - XO[3 * S + 1], X[2] - XO[3 * S + 2]};
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            double w = AO[S] * pow(r2, -0.5 * p);
+            phi += w;
+            for (int m = 0; m < 3; ++m) g[m] += -p * w / r2 * d[m];
+        }
+        E += a * phi;
+        if (!dE) continue;
+        for (int corner = 0; corner < 3; ++corner) {
+            const double* fj = V + 3 * (int64_t)F[3 * T + (corner + 1) % 3];
+            const double* fk = V + 3 * (int64_t)F[3 * T + (corner + 2) % 3];
+            double e[3] = {fk[0] - fj[0], fk[1] - fj[1], fk[2] - fj[2]};
+            double da[3] = {0.5 * (N[1] * e[2] - N[2] * e[1]), 0.5 * (N[2] * e[0] - N[0] * e[2]),
+                            0.5 * (N[0] * e[1] - N[1] * e[0])};
+            int64_t i = F[3 * T + corner];
+            for (int m = 0; m < 3; ++m) dE[3 * i + m] += a * g[m] / 3.0 + phi * da[m];
+        }
+    }
+    free(XO); free(AO);
+    return E;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Barnes-Hut approximation of the energy (Sec. 4.1) and its differential (Sec. 4.2).
  *
  * Tree (reading: the paper names a BVH with at most 8 faces per leaf and leaves the

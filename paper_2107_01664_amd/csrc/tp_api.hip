@@ -2,6 +2,7 @@
 // the hot path (energy, differential, fractional apply, preconditioner, descent step).
 #include "tp_solver.h"
 #include "tp_sobolev.h"
+#include "tp_obstacle.h"
 
 #include <algorithm>
 #include <cmath>
@@ -175,7 +176,8 @@ enum ScalarSlot {
     kSlotGX = 7,      // g.x per coordinate (3)
     kSlotS = 10,      // J Y, 2 x 2 entries of 3 coordinates each (12)
     kSlotR = 22,      // J y_g, 2 entries of 3 (6)
-    kNumSlots = 28
+    kSlotObs = 28,    // obstacle potential (unweighted)
+    kNumSlots = 29
 };
 
 // Ring of device tables for the multi-problem CG launches and their pinned staging.
@@ -254,6 +256,11 @@ struct tp_problem {
     DevBuf<double> gm_V, gm_Z, gm_w, gm_b, gm_r, gm_x, gm_small, gm_red, gm_Q, gm_Qn, gm_AQ, gm_one, gm_dinv,
         gm_sv, gm_sw, gm_smw;
     DevBuf<int32_t> gm_lab0;
+    // static obstacle (Sec. 7.2): face data of the obstacle mesh, per-face work arrays
+    DevBuf<double4> obs_x;
+    DevBuf<double> obs_e, obs_g;
+    int64_t obs_n = 0, obs_cap = 0;
+    double obs_p = 6.0, obs_w = 0.0;
     DevBuf<char> ub;
     DevBuf<double> cg_Z, cg_p, cg_red, cg_relres;
     DevBuf<unsigned> cg_bar;
@@ -303,7 +310,8 @@ struct tp_problem {
              pcg_rho.bytes() + pcg_red.bytes() + pcg_bp.bytes() + pcg_xp.bytes();
         b += gm_V.bytes() + gm_Z.bytes() + gm_w.bytes() + gm_b.bytes() + gm_r.bytes() + gm_x.bytes() +
              gm_small.bytes() + gm_red.bytes() + gm_Q.bytes() + gm_Qn.bytes() + gm_AQ.bytes() + gm_one.bytes() +
-             gm_lab0.bytes() + gm_dinv.bytes() + gm_sv.bytes() + gm_sw.bytes() + gm_smw.bytes();
+             gm_lab0.bytes() + gm_dinv.bytes() + gm_sv.bytes() + gm_sw.bytes() + gm_smw.bytes() + obs_x.bytes() +
+             obs_e.bytes() + obs_g.bytes();
         b += ml_r.bytes() + ml_p.bytes() + ml_s.bytes() + ml_m.bytes() + ml_an.bytes() + ml_v.bytes() +
              ml_shares.bytes() + ml_g.bytes() + ml_part.bytes() + ml_state.bytes();
         b += part.bytes() + gface.bytes() + zbuf.bytes() + scal.bytes() + red.bytes() + vol6.bytes() +
@@ -1826,6 +1834,18 @@ struct HostSolve2 {
 // x = -(y_g - Y S^{-1} J y_g); Armijo line search on E(f + tau x); corrective projection
 // f <- f + tau x - Y S^{-1} Phi(f + tau x) (Sec. 3.3, Sec. 5.3).
 
+// Obstacle potential at the current face data into slot kSlotObs, and its face partials in
+// obs_g ([7][nF], for launch_grad_gather).
+tp_status enqueue_obstacle(tp_problem* P)
+{
+    hipStream_t s = P->stream;
+    TP_TRY(P->obs_e.ensure((size_t)P->nF, s));
+    TP_TRY(P->obs_g.ensure((size_t)7 * P->nF, s));
+    TP_HIP(launch_obstacle_pairs(P->fd.dx, P->nF, P->obs_x.p, P->obs_cap, P->obs_p, P->obs_e.p, P->obs_g.p, P->nF, s));
+    TP_HIP(launch_dot_cols(P->obs_e.p, 1, nullptr, 0, P->nF, 1, P->red.p, P->scal.p + kSlotObs, s));
+    return TP_OK;
+}
+
 struct StepState {
     tp_problem* P = nullptr;
     tp_step_opts o;
@@ -1839,6 +1859,7 @@ struct StepState {
     double* dir_out = nullptr;
     bool alive() const { return st == TP_OK || st == TP_E_NOT_CONVERGED; }
     bool penalized() const { return o.area_penalty > 0.0 || o.volume_penalty > 0.0; }
+    bool obstacle() const { return P->obs_w > 0.0 && P->obs_n > 0; }
     // w_A (A / A0 - 1)^2 + w_V (V / V0 - 1)^2 (Sec. 7.2), A and V the total area and volume
     double penalty(double area, double vol) const
     {
@@ -1899,21 +1920,29 @@ tp_status step_group(std::vector<StepState*>& G)
     //     2 w_A (A / A0 - 1) / A0 dA + 2 w_V (V / V0 - 1) / V0 dV
     {
         Batch BP;
-        for (StepState* S : G)
-            if (S->penalized()) {
-                TP_TRY(enqueue_area_volume(S->P, S->P->V.p));   // face data describes V
-                BP.push_back(S->P);
-            }
+        for (StepState* S : G) {
+            if (S->penalized()) TP_TRY(enqueue_area_volume(S->P, S->P->V.p));   // face data describes V
+            if (S->obstacle()) TP_TRY(enqueue_obstacle(S->P));
+            if (S->penalized() || S->obstacle()) BP.push_back(S->P);
+        }
         if (!BP.empty()) {
             TP_TRY(enqueue_fetch(BP));
             TP_TRY(sync_batch(BP));
         }
         for (StepState* S : G) {
-            if (!S->penalized()) continue;
             tp_problem* P = S->P;
             const int64_t n = P->nV;
+            if (S->obstacle()) {   // w E_obs and its differential w dE_obs
+                const double w = P->obs_w;
+                const int c0 = 0;
+                S->pen0 += w * P->hs.p[kSlotObs];
+                TP_HIP(launch_grad_gather(P->V.p, P->F.p, n, P->nF, P->vf_off.p, P->vf_idx.p, P->obs_g.p, P->nF,
+                                          P->Vt.p, s));
+                TP_HIP(launch_axpy_block3(n, P->gbuf.p, 3, 1.0, P->Vt.p, 3, 1, &w, &c0, P->gbuf.p, 3, s));
+            }
+            if (!S->penalized()) continue;
             const double area = P->hs.p[kSlotArea], vol = P->hs.p[kSlotVol6] / 6.0;
-            S->pen0 = S->penalty(area, vol);
+            S->pen0 += S->penalty(area, vol);
             const int c0 = 0;
             if (S->o.area_penalty > 0.0) {
                 const double cA = 2.0 * S->o.area_penalty * (area / S->A0 - 1.0) / S->A0;
@@ -2079,6 +2108,7 @@ tp_status step_group(std::vector<StepState*>& G)
             ++P->geom_ver;
             P->geom_valid = false;
             if (S->penalized()) TP_TRY(enqueue_area_volume(P, P->Vt.p));
+            if (S->obstacle()) TP_TRY(enqueue_obstacle(P));
             BS.push_back(P);
         }
         TP_TRY(enqueue_energy(BS, kSlotE));
@@ -2092,7 +2122,8 @@ tp_status step_group(std::vector<StepState*>& G)
                 S->st = gs;
                 continue;
             }
-            const double Et = P->hs.p[kSlotE] + (S->penalized() ? S->penalty(P->hs.p[kSlotArea], P->hs.p[kSlotVol6] / 6.0) : 0.0);
+            const double Et = P->hs.p[kSlotE] + (S->penalized() ? S->penalty(P->hs.p[kSlotArea], P->hs.p[kSlotVol6] / 6.0) : 0.0) +
+                              (S->obstacle() ? P->obs_w * P->hs.p[kSlotObs] : 0.0);
             const bool valid = gs == TP_OK && finite(Et);
             const bool ok = valid && (!S->o.line_search || Et <= S->E0 + S->o.armijo_c * S->tau * S->R.slope);
             if (ok || !S->o.line_search) {
@@ -2147,6 +2178,7 @@ tp_status step_group(std::vector<StepState*>& G)
         P->fd_V = P->V.p;
         ++P->geom_ver;
         TP_TRY(enqueue_area_volume(P, P->V.p));
+        if (S->obstacle()) TP_TRY(enqueue_obstacle(P));
         BF.push_back(P);
         fin.push_back(S);
     }
@@ -2165,7 +2197,8 @@ tp_status step_group(std::vector<StepState*>& G)
         }
         P->geom_valid = true;
         constraint_values(*S, P->hs.p, S->R.phi_after);
-        S->R.E_new = P->hs.p[kSlotE] + S->penalty(P->hs.p[kSlotArea], P->hs.p[kSlotVol6] / 6.0);
+        S->R.E_new = P->hs.p[kSlotE] + S->penalty(P->hs.p[kSlotArea], P->hs.p[kSlotVol6] / 6.0) +
+                     (S->obstacle() ? P->obs_w * P->hs.p[kSlotObs] : 0.0);
     }
     // timings of the group (shared by its problems)
     const double t[8] = {tm.ms(0, 1), tm.ms(1, 2), tm.ms(1, 4), tm.ms(4, 5),
@@ -2438,6 +2471,56 @@ tp_status tp_problem_fractional_apply(tp_problem* P, const double* u, int k, dou
     TP_TRY(ensure_geometry(P));
     TP_TRY(run_fractional(P, u, k, k, Lu_out, k));
     TP_HIP(hipStreamSynchronize(P->stream));
+    return TP_OK;
+}
+
+tp_status tp_problem_set_obstacle(tp_problem* P, const double* Vo, int64_t nVo, const int32_t* Fo, int64_t nFo,
+                                  double p, double weight)
+{
+    TP_TRY(bind(P));
+    set_error("");
+    if (nFo == 0 || weight == 0.0) {   // remove the obstacle
+        P->obs_n = 0;
+        P->obs_w = 0.0;
+        return TP_OK;
+    }
+    if (!Vo || !Fo || nVo < 3 || nFo < 1) return fail(TP_E_INVALID_ARGUMENT, "obstacle needs Vo, Fo, nVo >= 3, nFo >= 1");
+    if (!(p > 0.0) || !(weight > 0.0) || !std::isfinite(p) || !std::isfinite(weight))
+        return fail(TP_E_INVALID_ARGUMENT, "obstacle exponent and weight must be positive and finite");
+    if (nFo > (int64_t)(INT32_MAX / 8)) return fail(TP_E_INVALID_ARGUMENT, "obstacle too large");
+    hipStream_t s = P->stream;
+    std::vector<int32_t> fh((size_t)3 * nFo);
+    TP_HIP(hipMemcpyAsync(fh.data(), Fo, sizeof(int32_t) * fh.size(), hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    for (int32_t v : fh)
+        if (v < 0 || (int64_t)v >= nVo) return fail(TP_E_INVALID_ARGUMENT, "obstacle face index out of range");
+    P->obs_cap = obstacle_capacity(nFo);
+    TP_TRY(P->obs_x.ensure((size_t)P->obs_cap, s));
+    TP_HIP(launch_obstacle_faces(Vo, Fo, nFo, P->obs_cap, P->obs_x.p, s));
+    TP_HIP(hipStreamSynchronize(s));
+    P->obs_n = nFo;
+    P->obs_p = p;
+    P->obs_w = weight;
+    return TP_OK;
+}
+
+tp_status tp_problem_obstacle_energy(tp_problem* P, double* E_out, double* dE_out)
+{
+    TP_TRY(bind(P));
+    if (!E_out) return fail(TP_E_INVALID_ARGUMENT, "E_out is NULL");
+    if (P->obs_n < 1) return fail(TP_E_INVALID_ARGUMENT, "no obstacle is set");
+    set_error("");
+    TP_TRY(ensure_geometry(P));
+    TP_TRY(ensure_vf(P));
+    const Batch B{P};
+    TP_TRY(enqueue_obstacle(P));
+    if (dE_out)
+        TP_HIP(launch_grad_gather(P->V.p, P->F.p, P->nV, P->nF, P->vf_off.p, P->vf_idx.p, P->obs_g.p, P->nF, dE_out,
+                                  P->stream));
+    TP_TRY(enqueue_fetch(B));
+    TP_TRY(sync_batch(B));
+    *E_out = P->hs.p[kSlotObs];
+    if (!std::isfinite(*E_out)) return fail(TP_E_NONFINITE, "non-finite obstacle potential (a barycenter on the obstacle?)");
     return TP_OK;
 }
 

@@ -1,0 +1,20 @@
+// Static obstacle potential (Sec. 7.2): a fixed mesh O repels the surface with
+//   E_obs = sum_T a_T sum_{S in O} a_O(S) |X_O(S) - X_T|^-p,
+// the potential of every face T of the surface evaluated at its barycenter and integrated
+// over its area.
+#pragma once
+#include "tp_internal.h"
+
+namespace tp {
+
+// Obstacle face data: (X_O, a_O) in FP64 for cap_o entries (padding: zero area, far away).
+int64_t obstacle_capacity(int64_t nFo);
+hipError_t launch_obstacle_faces(const double* Vo, const int32_t* Fo, int64_t nFo, int64_t cap_o, double4* xo,
+                                 hipStream_t s);
+// Per surface face T (dx: the surface's FP64 face data, nF faces): e[T] = a_T phi(T) and the
+// face partials of E_obs for the vertex chain rule, g = [7][gs]: dE/dX_T (3 rows), dE/dN_T = 0
+// (3 rows), dE/da_T = phi(T) (1 row).
+hipError_t launch_obstacle_pairs(const double4* dx, int64_t nF, const double4* xo, int64_t cap_o, double p,
+                                 double* e, double* g, int64_t gs, hipStream_t s);
+
+}  // namespace tp

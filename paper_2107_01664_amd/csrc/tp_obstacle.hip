@@ -1,0 +1,93 @@
+// Static obstacle potential (Sec. 7.2) on the GPU, FP64 pair terms: one thread per surface
+// face T, the obstacle's faces streamed through LDS in tiles of kTileJ (every lane reads the
+// same obstacle face).  Per pair, with d = X_T - X_O(S) and r2 = |d|^2:
+//   w = a_O(S) r2^(-p/2),  phi(T) += w,  dphi/dX_T += -p w d / r2.
+// Sums run over the obstacle in a fixed order, so results are reproducible.
+#include "tp_obstacle.h"
+
+namespace tp {
+
+namespace {
+
+inline unsigned nblk(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+__global__ void k_obs_faces(const double* __restrict__ Vo, const int32_t* __restrict__ Fo, int64_t nFo,
+                            int64_t cap_o, double4* __restrict__ xo)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= cap_o) return;
+    if (t >= nFo) {   // padding: zero area far away (its terms are 0 * tiny)
+        xo[t] = make_double4(1e15, 1e15, 1e15, 0.0);
+        return;
+    }
+    const double* a = Vo + 3 * (int64_t)Fo[3 * t];
+    const double* b = Vo + 3 * (int64_t)Fo[3 * t + 1];
+    const double* c = Vo + 3 * (int64_t)Fo[3 * t + 2];
+    const double e1[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    const double e2[3] = {c[0] - a[0], c[1] - a[1], c[2] - a[2]};
+    const double cr[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    xo[t] = make_double4((a[0] + b[0] + c[0]) / 3.0, (a[1] + b[1] + c[1]) / 3.0, (a[2] + b[2] + c[2]) / 3.0,
+                         0.5 * sqrt(cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2]));
+}
+
+template <bool P6>
+__global__ __launch_bounds__(kBlock) void k_obs_pairs(const double4* __restrict__ dx, int64_t nF,
+                                                      const double4* __restrict__ xo, int64_t cap_o, double p,
+                                                      double* __restrict__ e, double* __restrict__ g, int64_t gs)
+{
+    __shared__ double4 s_o[kTileJ];
+    const int64_t T = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const double4 x = dx[T < nF ? T : 0];
+    double phi = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int64_t j0 = 0; j0 < cap_o; j0 += kTileJ) {
+        __syncthreads();
+        for (int q = threadIdx.x; q < kTileJ; q += kBlock) s_o[q] = xo[j0 + q];
+        __syncthreads();
+        for (int q = 0; q < kTileJ; ++q) {
+            const double4 o = s_o[q];
+            const double d0 = x.x - o.x, d1 = x.y - o.y, d2 = x.z - o.z;
+            const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+            const double inv = 1.0 / r2;
+            const double w = o.w * (P6 ? inv * inv * inv : pow(r2, -0.5 * p));
+            phi += w;
+            const double c = -p * w * inv;
+            g0 += c * d0;
+            g1 += c * d1;
+            g2 += c * d2;
+        }
+    }
+    if (T >= nF) return;
+    e[T] = x.w * phi;
+    g[T] = x.w * g0;
+    g[gs + T] = x.w * g1;
+    g[2 * gs + T] = x.w * g2;
+    g[3 * gs + T] = 0.0;
+    g[4 * gs + T] = 0.0;
+    g[5 * gs + T] = 0.0;
+    g[6 * gs + T] = phi;
+}
+
+}  // namespace
+
+int64_t obstacle_capacity(int64_t nFo) { return (std::max<int64_t>(nFo, 1) + kTileJ - 1) / kTileJ * kTileJ; }
+
+hipError_t launch_obstacle_faces(const double* Vo, const int32_t* Fo, int64_t nFo, int64_t cap_o, double4* xo,
+                                 hipStream_t s)
+{
+    if (cap_o % kTileJ != 0 || cap_o < nFo) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_obs_faces, dim3(nblk(cap_o)), dim3(256), 0, s, Vo, Fo, nFo, cap_o, xo);
+    return hipGetLastError();
+}
+
+hipError_t launch_obstacle_pairs(const double4* dx, int64_t nF, const double4* xo, int64_t cap_o, double p,
+                                 double* e, double* g, int64_t gs, hipStream_t s)
+{
+    if (cap_o % kTileJ != 0 || nF < 1 || gs < nF) return hipErrorInvalidValue;
+    if (p == 6.0)
+        hipLaunchKernelGGL(k_obs_pairs<true>, dim3(nblk(nF, kBlock)), dim3(kBlock), 0, s, dx, nF, xo, cap_o, p, e, g, gs);
+    else
+        hipLaunchKernelGGL(k_obs_pairs<false>, dim3(nblk(nF, kBlock)), dim3(kBlock), 0, s, dx, nF, xo, cap_o, p, e, g, gs);
+    return hipGetLastError();
+}
+
+}  // namespace tp

@@ -34,7 +34,7 @@ EXPORTED = [
     "tp_precond_apply", "tp_problem_create", "tp_problem_destroy", "tp_problem_set_vertices",
     "tp_problem_get_vertices", "tp_problem_energy", "tp_problem_gradient",
     "tp_problem_fractional_apply", "tp_sobolev_apply", "tp_problem_sobolev_apply",
-    "tp_problem_sobolev_solve",
+    "tp_problem_sobolev_solve", "tp_problem_set_obstacle", "tp_problem_obstacle_energy",
     "tp_problem_precond_apply", "tp_step_opts_default",
     "tp_precond_step", "tp_last_error", "tp_profile_enable", "tp_profile_reset", "tp_profile_get",
     "tp_problem_poisson_solve", "tp_batch_step", "tp_problem_device_bytes",
@@ -122,6 +122,8 @@ def lib() -> ctypes.CDLL:
         "tp_problem_fractional_apply": [vp, vp, i32, vp],
         "tp_sobolev_apply": [vp, i64, vp, i64, P(Params), vp, i32, vp, vp],
         "tp_problem_sobolev_apply": [vp, vp, i32, vp],
+        "tp_problem_set_obstacle": [vp, vp, i64, vp, i64, ctypes.c_double, ctypes.c_double],
+        "tp_problem_obstacle_energy": [vp, P(d), vp],
         "tp_problem_sobolev_solve": [vp, vp, i32, ctypes.c_double, i32, i32, i32, vp, P(GmresReport)],
         "tp_problem_precond_apply": [vp, vp, i32, vp, P(SolveReport)],
         "tp_problem_poisson_solve": [vp, vp, i32, vp, P(SolveReport)],
@@ -335,6 +337,18 @@ class Problem:
         rep = {"iters": r.iters, "cycles": r.cycles, "relres": r.relres,
                "precond_cg_iters": r.precond_cg_iters, "t_ms": r.t_ms, "omega": r.omega, "status": st}
         return (x[:, 0] if squeeze else x), rep
+
+    def set_obstacle(self, Vo, Fo, p: float = 6.0, weight: float = 1.0):
+        """Static obstacle mesh (device tensors) with potential exponent p and weight."""
+        Vo, Fo = _mesh(Vo, Fo)
+        _check(lib().tp_problem_set_obstacle(self._h, Vo.data_ptr(), Vo.shape[0], Fo.data_ptr(), Fo.shape[0],
+                                             p, weight))
+
+    def obstacle_energy(self, out=None):
+        dE = out if out is not None else torch.empty((self.nV, 3), dtype=torch.float64, device=self.device)
+        E = ctypes.c_double()
+        _check(lib().tp_problem_obstacle_energy(self._h, ctypes.byref(E), dE.data_ptr()))
+        return E.value, dE
 
     def sobolev_apply(self, u, out=None):
         squeeze = u.dim() == 1

@@ -734,3 +734,46 @@ def test_step_penalties(tp, meshes):
     E_new = O.energy(Vn, m.F) + O.penalty_terms(Vn, m.F, A0, V0, 5.0, 5.0)[0]
     assert abs(rep.E_new - E_new) <= TOL32 * E_new
     assert rep.slope < 0
+
+
+def _obstacle_mesh():
+    ob = mg.add_noise(mg.icosphere(2), 0.02, 9)   # 320 faces (a ragged last LDS tile)
+    return 0.4 * ob.V + np.array([1.6, 0.3, -0.1]), ob.F
+
+
+@pytest.mark.parametrize("p", [6.0, 4.5])
+def test_obstacle_energy(tp, meshes, p):
+    """Obstacle potential and its differential (FP64 pair terms) against the oracle."""
+    m = meshes["small_sphere"]
+    Vo, Fo = _obstacle_mesh()
+    print(f"[parity] obstacle potential p={p}", flush=True)
+    E0, g0 = O.obstacle(m.V, m.F, Vo, Fo, p)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        P.set_obstacle(dev(Vo), dev(Fo, torch.int32), p=p, weight=1.0)
+        E1, g1 = P.obstacle_energy()
+    assert abs(E1 - E0) <= 1e-12 * E0, (E1, E0)
+    assert rel(g1.cpu().numpy(), g0) <= 1e-11
+
+
+def test_step_obstacle(tp, meshes):
+    """A step with the obstacle potential (weight 0.05) and both hard constraints, fixed tau,
+    against the oracle's step; the total objective in the report."""
+    m = meshes["small_sphere"]
+    Vo, Fo = _obstacle_mesh()
+    print("[parity] step with an obstacle", flush=True)
+    tau, w = 2e-3, 0.05
+    ref = O.precond_step(m.V, m.F, tau=tau, line_search=False, obstacle_mesh=(Vo, Fo), obstacle_weight=w)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        P.set_obstacle(dev(Vo), dev(Fo, torch.int32), p=6.0, weight=w)
+        d = torch.empty((m.nV, 3), dtype=torch.float64, device="cuda")
+        rep = P.step(tp.step_opts(tau0=tau, line_search=0), direction=d)
+        Vn = P.vertices().cpu().numpy()
+        with pytest.raises(tp.TpError):
+            P.set_obstacle(dev(Vo), dev(Fo, torch.int32), p=-1.0, weight=1.0)
+    x = d.cpu().numpy()
+    print("  direction error", rel(x, ref.direction), flush=True)
+    assert rel(x, ref.direction) <= 1e-4, rel(x, ref.direction)
+    assert rel(Vn - m.V, ref.V - m.V) <= 1e-4
+    assert abs(rep.E - ref.E) <= TOL32 * ref.E
+    E_new = O.energy(Vn, m.F) + w * O.obstacle(Vn, m.F, Vo, Fo, 6.0, False)[0]
+    assert abs(rep.E_new - E_new) <= TOL32 * E_new

@@ -537,3 +537,30 @@ def test_penalty_potentials(noisy2):
     Vn = res.V
     E_new = O.energy(Vn, F) + O.penalty_terms(Vn, F, A0, V0, 3.0, 2.0)[0]
     assert E_new < res.E
+
+
+def test_obstacle_potential(noisy2):
+    """Obstacle potential of Sec. 7.2: differential against central differences, the scaling
+    law E(lambda f, lambda f_O) = lambda^(4 - p) E, invariance under a rigid motion of both
+    meshes, and a far obstacle seen as one point mass: E -> a_O,total sum_T a_T |X_T - c|^-p."""
+    V, F = noisy2.V, noisy2.F
+    ob = mg.add_noise(mg.icosphere(1), 0.02, 9)
+    Vo = 0.4 * ob.V + np.array([2.2, 0.3, -0.1])
+    E, g = O.obstacle(V, F, Vo, ob.F, 6.0)
+    rng = np.random.default_rng(10)
+    for _ in range(3):
+        d = rng.standard_normal(V.shape)
+        h = 1e-6
+        fd = (O.obstacle(V + h * d, F, Vo, ob.F, 6.0, False)[0] - O.obstacle(V - h * d, F, Vo, ob.F, 6.0, False)[0]) / (2 * h)
+        assert abs(fd - np.vdot(g, d)) <= 1e-6 * abs(fd), (fd, np.vdot(g, d))
+    for p in (6.0, 4.5):
+        E1 = O.obstacle(V, F, Vo, ob.F, p, False)[0]
+        assert abs(O.obstacle(1.7 * V, F, 1.7 * Vo, ob.F, p, False)[0] - 1.7 ** (4 - p) * E1) <= 1e-12 * E1
+    Q = random_rotation(RNG)
+    assert abs(O.obstacle(V @ Q.T + 1.0, F, Vo @ Q.T + 1.0, ob.F, 6.0, False)[0] - E) <= 1e-12 * E
+    far = np.array([200.0, 0.0, 0.0])
+    Ef = O.obstacle(V, F, 0.4 * ob.V + far, ob.F, 6.0, False)[0]
+    X, _, a = O.faces(V, F)
+    _, _, ao = O.faces(0.4 * ob.V + far, ob.F)
+    approx = ao.sum() * np.sum(a * np.sum((X - far) ** 2, 1) ** -3.0)
+    assert abs(Ef - approx) <= 1e-3 * approx
