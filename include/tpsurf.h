@@ -263,6 +263,10 @@ typedef struct {
                                 the tangent-point energy plus the potentials: their
                                 gradients join dE, the line search and E / E_new of the
                                 report include them                                       */
+    int    barycenter_motion; /* 1: barycenter motions (Sec. 7.1.1): the solve removes every
+                                component's mean, and the translation by minus the
+                                vertex-area-weighted mean of dE (of the total objective)
+                                over the component is added back to the direction; default 0 */
 } tp_step_opts;
 
 TP_API tp_status tp_step_opts_default(tp_step_opts* o);

@@ -481,7 +481,8 @@ ARMIJO_MAX_BACKTRACKS = 30
 def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=None,
                  line_search=True, constrain_area=True, constrain_volume=True,
                  area_target=None, volume_target=None, inverse=None, area_penalty=0.0,
-                 volume_penalty=0.0, obstacle_mesh=None, obstacle_p=6.0, obstacle_weight=0.0):
+                 volume_penalty=0.0, obstacle_mesh=None, obstacle_p=6.0, obstacle_weight=0.0,
+                 barycenter_motion=False):
     """One constrained descent step with A~^{-1} in place of A_3^{-1}, or with the map R -> Y
     given as `inverse` (for instance A_3^{-1} from dense_sobolev_inverse; Sec. 5.4, step 3).
 
@@ -497,7 +498,9 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     With area_penalty / volume_penalty > 0 the objective is E plus the potentials of Sec. 7.2
     (penalty_terms): their gradients join g and the line search, and E of the result is the
     total.  obstacle_mesh = (Vo, Fo) with obstacle_weight > 0 adds weight x the obstacle
-    potential (obstacle) to the objective in the same way."""
+    potential (obstacle) to the objective in the same way.  barycenter_motion adds to x, per
+    connected component, minus the vertex-area-weighted mean of g (Sec. 7.1.1; vertex area
+    = a third of the areas of the faces around the vertex)."""
     V, F = _prep(V, F)
     nV = V.shape[0]
     if sigma is None:
@@ -539,6 +542,14 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
         x = -(yg - sum(mu[m] * YJ[m] for m in range(k)))
     else:
         x = -yg
+    if barycenter_motion:
+        Af = faces(V, F)[2]
+        av = np.zeros(nV)
+        for c in range(3):
+            np.add.at(av, F[:, c], Af / 3.0)
+        for lab in np.unique(labels):
+            idx = labels == lab
+            x[idx] -= (av[idx, None] * g[idx]).sum(0) / av[idx].sum()
     phi_before = np.array([fns[m](V, F) - targets[m] for m in range(k)])
     slope = float(np.vdot(g, x))
     if tau is None:

@@ -258,7 +258,7 @@ struct tp_problem {
     DevBuf<int32_t> gm_lab0;
     // static obstacle (Sec. 7.2): face data of the obstacle mesh, per-face work arrays
     DevBuf<double4> obs_x;
-    DevBuf<double> obs_e, obs_g;
+    DevBuf<double> obs_e, obs_g, bm_area, bm_t;
     int64_t obs_n = 0, obs_cap = 0;
     double obs_p = 6.0, obs_w = 0.0;
     DevBuf<char> ub;
@@ -311,7 +311,7 @@ struct tp_problem {
         b += gm_V.bytes() + gm_Z.bytes() + gm_w.bytes() + gm_b.bytes() + gm_r.bytes() + gm_x.bytes() +
              gm_small.bytes() + gm_red.bytes() + gm_Q.bytes() + gm_Qn.bytes() + gm_AQ.bytes() + gm_one.bytes() +
              gm_lab0.bytes() + gm_dinv.bytes() + gm_sv.bytes() + gm_sw.bytes() + gm_smw.bytes() + obs_x.bytes() +
-             obs_e.bytes() + obs_g.bytes();
+             obs_e.bytes() + obs_g.bytes() + bm_area.bytes() + bm_t.bytes();
         b += ml_r.bytes() + ml_p.bytes() + ml_s.bytes() + ml_m.bytes() + ml_an.bytes() + ml_v.bytes() +
              ml_shares.bytes() + ml_g.bytes() + ml_part.bytes() + ml_state.bytes();
         b += part.bytes() + gface.bytes() + zbuf.bytes() + scal.bytes() + red.bytes() + vol6.bytes() +
@@ -2058,6 +2058,30 @@ tp_status step_group(std::vector<StepState*>& G)
         const double cf[2] = {S->mu[0], S->mu[1]};
         const int cols[2] = {3, 6};
         TP_HIP(launch_axpy_block3(n, P->Y.p, ncol, -1.0, P->Y.p, ncol, S->kc, cf, cols, P->dir.p, 3, s));
+        if (S->o.barycenter_motion) {
+            // barycenter motions (Sec. 7.1.1): add back to the direction, per component, the
+            // translation by minus the vertex-area-weighted mean of g (face data describes V)
+            const int nc = P->ncomp;
+            TP_TRY(P->bm_area.ensure((size_t)n, s));
+            TP_TRY(P->bm_t.ensure((size_t)3 * nc, s));
+            TP_HIP(launch_vertex_area(n, P->vf_off.p, P->vf_idx.p, P->fd.dx, P->bm_area.p, s));
+            std::vector<double> gh((size_t)3 * n), ah((size_t)n), t((size_t)3 * nc, 0.0), w((size_t)nc, 0.0);
+            std::vector<int32_t> lab((size_t)n);
+            TP_HIP(hipMemcpyAsync(gh.data(), P->gbuf.p, sizeof(double) * gh.size(), hipMemcpyDeviceToHost, s));
+            TP_HIP(hipMemcpyAsync(ah.data(), P->bm_area.p, sizeof(double) * ah.size(), hipMemcpyDeviceToHost, s));
+            TP_HIP(hipMemcpyAsync(lab.data(), P->comp.p, sizeof(int32_t) * lab.size(), hipMemcpyDeviceToHost, s));
+            TP_HIP(hipStreamSynchronize(s));
+            for (int64_t v = 0; v < n; ++v) {   // vertex order: fixed
+                const int c = lab[v];
+                w[c] += ah[v];
+                for (int q = 0; q < 3; ++q) t[3 * c + q] += ah[v] * gh[3 * v + q];
+            }
+            for (int c = 0; c < nc; ++c)
+                for (int q = 0; q < 3; ++q) t[3 * c + q] = w[c] > 0.0 ? -t[3 * c + q] / w[c] : 0.0;
+            TP_HIP(hipMemcpyAsync(P->bm_t.p, t.data(), sizeof(double) * t.size(), hipMemcpyHostToDevice, s));
+            TP_HIP(launch_add_translation(P->dir.p, P->comp.p, P->bm_t.p, n, s));
+            TP_HIP(hipStreamSynchronize(s));
+        }
         TP_HIP(launch_dot_cols(P->gbuf.p, 3, P->gbuf.p, 3, n, 3, P->red.p, P->scal.p + kSlotGG, s));
         TP_HIP(launch_dot_cols(P->gbuf.p, 3, P->dir.p, 3, n, 3, P->red.p, P->scal.p + kSlotGX, s));
         TP_HIP(launch_max_rownorm3(P->dir.p, n, P->red.p, P->scal.p + kSlotMax, s));
@@ -2238,6 +2262,10 @@ tp_status run_step_batch(tp_problem* const* probs, int n, const tp_step_opts* op
             T.st = fail(TP_E_INVALID_ARGUMENT, "max_backtracks must be >= 0");
             continue;
         }
+        if (T.o.barycenter_motion != 0 && T.o.barycenter_motion != 1) {
+            T.st = fail(TP_E_INVALID_ARGUMENT, "barycenter_motion must be 0 or 1");
+            continue;
+        }
         if (!(T.o.area_penalty >= 0.0) || !(T.o.volume_penalty >= 0.0)) {
             T.st = fail(TP_E_INVALID_ARGUMENT, "penalty weights must be >= 0");
             continue;
@@ -2403,6 +2431,7 @@ tp_status tp_step_opts_default(tp_step_opts* o)
     o->solver_maxiter = 300;
     o->area_penalty = 0.0;
     o->volume_penalty = 0.0;
+    o->barycenter_motion = 0;
     return TP_OK;
 }
 

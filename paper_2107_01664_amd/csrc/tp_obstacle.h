@@ -17,4 +17,10 @@ hipError_t launch_obstacle_faces(const double* Vo, const int32_t* Fo, int64_t nF
 hipError_t launch_obstacle_pairs(const double4* dx, int64_t nF, const double4* xo, int64_t cap_o, double p,
                                  double* e, double* g, int64_t gs, hipStream_t s);
 
+// Vertex areas a(v) = sum of a_S / 3 over the faces S around v (dx: FP64 face data).
+hipError_t launch_vertex_area(int64_t nV, const int32_t* vf_off, const int32_t* vf_idx, const double4* dx,
+                              double* out, hipStream_t s);
+// x[v] += t[label[v]] (n x 3 rows, t ncomp x 3).
+hipError_t launch_add_translation(double* x, const int32_t* label, const double* t, int64_t n, hipStream_t s);
+
 }  // namespace tp

@@ -67,7 +67,38 @@ __global__ __launch_bounds__(kBlock) void k_obs_pairs(const double4* __restrict_
     g[6 * gs + T] = phi;
 }
 
+__global__ void k_vertex_area(int64_t nV, const int32_t* __restrict__ vf_off, const int32_t* __restrict__ vf_idx,
+                              const double4* __restrict__ dx, double* __restrict__ out)
+{
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nV) return;
+    double a = 0.0;
+    for (int32_t q = vf_off[v]; q < vf_off[v + 1]; ++q) a += dx[vf_idx[q] / 3].w / 3.0;
+    out[v] = a;
+}
+
+__global__ void k_add_translation(double* __restrict__ x, const int32_t* __restrict__ label,
+                                  const double* __restrict__ t, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= 3 * n) return;
+    x[i] += t[3 * (int64_t)label[i / 3] + i % 3];
+}
+
 }  // namespace
+
+hipError_t launch_vertex_area(int64_t nV, const int32_t* vf_off, const int32_t* vf_idx, const double4* dx,
+                              double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_vertex_area, dim3(nblk(nV)), dim3(256), 0, s, nV, vf_off, vf_idx, dx, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_add_translation(double* x, const int32_t* label, const double* t, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_translation, dim3(nblk(3 * n)), dim3(256), 0, s, x, label, t, n);
+    return hipGetLastError();
+}
 
 int64_t obstacle_capacity(int64_t nFo) { return (std::max<int64_t>(nFo, 1) + kTileJ - 1) / kTileJ * kTileJ; }
 

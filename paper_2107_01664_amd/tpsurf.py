@@ -70,7 +70,8 @@ class StepOpts(ctypes.Structure):
                 ("constrain_area", ctypes.c_int), ("constrain_volume", ctypes.c_int),
                 ("area_target", ctypes.c_double), ("volume_target", ctypes.c_double),
                 ("solver", ctypes.c_int), ("solver_rtol", ctypes.c_double), ("solver_maxiter", ctypes.c_int),
-                ("area_penalty", ctypes.c_double), ("volume_penalty", ctypes.c_double)]
+                ("area_penalty", ctypes.c_double), ("volume_penalty", ctypes.c_double),
+                ("barycenter_motion", ctypes.c_int)]
 
 
 class StepReport(ctypes.Structure):

@@ -777,3 +777,21 @@ def test_step_obstacle(tp, meshes):
     assert abs(rep.E - ref.E) <= TOL32 * ref.E
     E_new = O.energy(Vn, m.F) + w * O.obstacle(Vn, m.F, Vo, Fo, 6.0, False)[0]
     assert abs(rep.E_new - E_new) <= TOL32 * E_new
+
+
+def test_step_barycenter_motion(tp, meshes):
+    """Barycenter motions on two linked tori (per-component translations added back), fixed
+    tau, against the oracle's step."""
+    m = meshes["linked_small"]
+    print("[parity] step with barycenter motions", flush=True)
+    tau = 2e-3
+    ref = O.precond_step(m.V, m.F, tau=tau, line_search=False, barycenter_motion=True)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        d = torch.empty((m.nV, 3), dtype=torch.float64, device="cuda")
+        rep = P.step(tp.step_opts(tau0=tau, line_search=0, barycenter_motion=1), direction=d)
+        Vn = P.vertices().cpu().numpy()
+    x = d.cpu().numpy()
+    print("  direction error", rel(x, ref.direction), flush=True)
+    assert rel(x, ref.direction) <= 1e-4, rel(x, ref.direction)
+    assert rel(Vn - m.V, ref.V - m.V) <= 1e-4
+    assert abs(rep.slope - float(np.vdot(O.gradient(m.V, m.F)[1], ref.direction))) <= 1e-4 * abs(rep.slope)

@@ -564,3 +564,25 @@ def test_obstacle_potential(noisy2):
     _, _, ao = O.faces(0.4 * ob.V + far, ob.F)
     approx = ao.sum() * np.sum(a * np.sum((X - far) ** 2, 1) ** -3.0)
     assert abs(Ef - approx) <= 1e-3 * approx
+
+
+def test_barycenter_motion():
+    """Barycenter motions (Sec. 7.1.1) on two linked tori: the direction differs from the
+    plain one by a constant per component, minus the vertex-area-weighted mean of dE there
+    (vertex areas from a dense vertex-face incidence matrix)."""
+    m = mg.linked_tori(12, 6, 1.0, 0.25, 1.0)
+    kw = dict(tau=1e-3, line_search=False)
+    x0 = O.precond_step(m.V, m.F, **kw).direction
+    x1 = O.precond_step(m.V, m.F, barycenter_motion=True, **kw).direction
+    _, g = O.gradient(m.V, m.F)
+    _, labels = O.components(m.F, m.nV)
+    _, _, a = O.faces(m.V, m.F)
+    M = np.zeros((m.nV, m.F.shape[0]))
+    M[m.F[:, 0], np.arange(m.F.shape[0])] = 1.0
+    M[m.F[:, 1], np.arange(m.F.shape[0])] = 1.0
+    M[m.F[:, 2], np.arange(m.F.shape[0])] = 1.0
+    av = M @ a / 3.0
+    for lab in np.unique(labels):
+        idx = labels == lab
+        t = -(av[idx] @ g[idx]) / av[idx].sum()
+        assert np.abs(x1[idx] - x0[idx] - t).max() <= 1e-12 * np.abs(x0).max()
