@@ -188,6 +188,20 @@ TP_API tp_status tp_problem_set_obstacle(tp_problem* prob, const double* Vo, int
  * differential with respect to the surface's vertex positions. */
 TP_API tp_status tp_problem_obstacle_energy(tp_problem* prob, double* E_out, double* dE_out);
 
+/* Implicit obstacles and attractors (Sec. 7.2) on analytic signed distances d: kind 0 a
+ * plane, d(x) = (q . x - c) / |q|; kind 1 a sphere, d(x) = |x - q| - c (c > 0 the radius;
+ * q: host pointer to 3 doubles).  Potential weight * d^-p for an obstacle (attract = 0; a
+ * face barycenter with d <= 0 makes it non-finite, and the line search rejects such steps),
+ * weight * |d|^p for an attractor (attract = 1), evaluated at the face barycenters and
+ * integrated with the face areas, summed over the primitives (at most 8) and added to the
+ * objective of every later step.  kind < 0 removes them all.  TP_E_INVALID_ARGUMENT for a
+ * bad kind, p <= 0, weight <= 0, a zero plane normal or radius, or a ninth primitive. */
+TP_API tp_status tp_problem_add_implicit(tp_problem* prob, int kind, const double* q, double c, double p,
+                                         double weight, int attract);
+/* E_out = the weighted sum of the implicit potentials at the current vertices; dE_out
+ * (device nV x 3, or NULL) its differential. */
+TP_API tp_status tp_problem_implicit_energy(tp_problem* prob, double* E_out, double* dE_out);
+
 /* Report of one GMRES solve with A (tp_problem_sobolev_solve). */
 typedef struct {
     int    iters;             /* GMRES iterations (one preconditioner and one A product each) */

@@ -482,7 +482,7 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
                  line_search=True, constrain_area=True, constrain_volume=True,
                  area_target=None, volume_target=None, inverse=None, area_penalty=0.0,
                  volume_penalty=0.0, obstacle_mesh=None, obstacle_p=6.0, obstacle_weight=0.0,
-                 barycenter_motion=False):
+                 barycenter_motion=False, implicit=None):
     """One constrained descent step with A~^{-1} in place of A_3^{-1}, or with the map R -> Y
     given as `inverse` (for instance A_3^{-1} from dense_sobolev_inverse; Sec. 5.4, step 3).
 
@@ -517,6 +517,9 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     if use_obs:
         eo, go = obstacle(V, F, obstacle_mesh[0], obstacle_mesh[1], obstacle_p)
         E0, g = E0 + obstacle_weight * eo, g + obstacle_weight * go
+    if implicit:
+        ei, gi = implicit_potential(V, F, implicit)
+        E0, g = E0 + ei, g + gi
 
     def objective(Vx):
         e = energy(Vx, F, alpha, beta)
@@ -524,6 +527,8 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
             e += penalty_terms(Vx, F, A0, V0, area_penalty, volume_penalty)[0]
         if use_obs:
             e += obstacle_weight * obstacle(Vx, F, obstacle_mesh[0], obstacle_mesh[1], obstacle_p, False)[0]
+        if implicit:
+            e += implicit_potential(Vx, F, implicit, False)[0]
         return e
     rows, targets, fns = [], [], []
     if constrain_area:
@@ -586,6 +591,48 @@ def obstacle(V, F, Vo, Fo, p=6.0, with_grad=True):
     E = lib().tpo_obstacle(_d(V), V.shape[0], _i(F), F.shape[0], _d(Vo), _i(Fo), Fo.shape[0], p,
                            _d(dE) if with_grad else None)
     return float(E), dE
+
+
+def implicit_potential(V, F, prims, with_grad=True):
+    """Implicit obstacles and attractors of Sec. 7.2, evaluated at the face barycenters and
+    integrated with the face areas: sum_k w_k sum_T a_T phi_k(X_T), phi = d^-p (obstacle) or
+    |d|^p (attractor); d the signed distance to a plane {x : q.x = c} (kind 0, q normalised
+    with c) or a sphere of center q and radius c (kind 1).  prims: list of dicts with keys
+    kind, q, c, p, w, attract.  Returns (E, dE) with dE by the chain rule through X_T (1/3
+    per corner) and a_T (N_T x (f_k - f_j) / 2 per corner i, cyclic)."""
+    V, F = _prep(V, F)
+    X, N, a = faces(V, F)
+    phi = np.zeros(len(a))
+    dphi = np.zeros_like(X)
+    for pr in prims:
+        q = np.asarray(pr["q"], dtype=np.float64)
+        if pr["kind"] == 0:
+            nq = np.linalg.norm(q)
+            n = np.broadcast_to(q / nq, X.shape)
+            d = X @ (q / nq) - pr["c"] / nq
+        else:
+            r = X - q
+            rn = np.linalg.norm(r, axis=1)
+            n = r / rn[:, None]
+            d = rn - pr["c"]
+        p, w = pr["p"], pr["w"]
+        if pr.get("attract", False):
+            f = np.abs(d) ** p
+            df = p * np.abs(d) ** (p - 1.0) * np.sign(d)
+        else:
+            f = d ** (-p)
+            df = -p * d ** (-p - 1.0)
+        phi += w * f
+        dphi += (w * df)[:, None] * n
+    E = float(np.sum(a * phi))
+    if not with_grad:
+        return E, None
+    dE = np.zeros_like(V)
+    for corner in range(3):
+        i, j, k = F[:, corner], F[:, (corner + 1) % 3], F[:, (corner + 2) % 3]
+        da = 0.5 * np.cross(N, V[k] - V[j])
+        np.add.at(dE, i, a[:, None] * dphi / 3.0 + phi[:, None] * da)
+    return E, dE
 
 
 def penalty_terms(V, F, A0, V0, area_weight, volume_weight):

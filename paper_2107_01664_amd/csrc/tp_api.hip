@@ -177,7 +177,8 @@ enum ScalarSlot {
     kSlotS = 10,      // J Y, 2 x 2 entries of 3 coordinates each (12)
     kSlotR = 22,      // J y_g, 2 entries of 3 (6)
     kSlotObs = 28,    // obstacle potential (unweighted)
-    kNumSlots = 29
+    kSlotImp = 29,    // implicit obstacles and attractors (weighted)
+    kNumSlots = 30
 };
 
 // Ring of device tables for the multi-problem CG launches and their pinned staging.
@@ -258,7 +259,8 @@ struct tp_problem {
     DevBuf<int32_t> gm_lab0;
     // static obstacle (Sec. 7.2): face data of the obstacle mesh, per-face work arrays
     DevBuf<double4> obs_x;
-    DevBuf<double> obs_e, obs_g, bm_area, bm_t;
+    DevBuf<double> obs_e, obs_g, bm_area, bm_t, imp_e, imp_g;
+    ImplicitSet imp;
     int64_t obs_n = 0, obs_cap = 0;
     double obs_p = 6.0, obs_w = 0.0;
     DevBuf<char> ub;
@@ -311,7 +313,7 @@ struct tp_problem {
         b += gm_V.bytes() + gm_Z.bytes() + gm_w.bytes() + gm_b.bytes() + gm_r.bytes() + gm_x.bytes() +
              gm_small.bytes() + gm_red.bytes() + gm_Q.bytes() + gm_Qn.bytes() + gm_AQ.bytes() + gm_one.bytes() +
              gm_lab0.bytes() + gm_dinv.bytes() + gm_sv.bytes() + gm_sw.bytes() + gm_smw.bytes() + obs_x.bytes() +
-             obs_e.bytes() + obs_g.bytes() + bm_area.bytes() + bm_t.bytes();
+             obs_e.bytes() + obs_g.bytes() + bm_area.bytes() + bm_t.bytes() + imp_e.bytes() + imp_g.bytes();
         b += ml_r.bytes() + ml_p.bytes() + ml_s.bytes() + ml_m.bytes() + ml_an.bytes() + ml_v.bytes() +
              ml_shares.bytes() + ml_g.bytes() + ml_part.bytes() + ml_state.bytes();
         b += part.bytes() + gface.bytes() + zbuf.bytes() + scal.bytes() + red.bytes() + vol6.bytes() +
@@ -1846,6 +1848,17 @@ tp_status enqueue_obstacle(tp_problem* P)
     return TP_OK;
 }
 
+// Implicit potentials at the current face data into slot kSlotImp, face partials in imp_g.
+tp_status enqueue_implicit(tp_problem* P)
+{
+    hipStream_t s = P->stream;
+    TP_TRY(P->imp_e.ensure((size_t)P->nF, s));
+    TP_TRY(P->imp_g.ensure((size_t)7 * P->nF, s));
+    TP_HIP(launch_implicit(P->fd.dx, P->nF, P->imp, P->imp_e.p, P->imp_g.p, P->nF, s));
+    TP_HIP(launch_dot_cols(P->imp_e.p, 1, nullptr, 0, P->nF, 1, P->red.p, P->scal.p + kSlotImp, s));
+    return TP_OK;
+}
+
 struct StepState {
     tp_problem* P = nullptr;
     tp_step_opts o;
@@ -1860,6 +1873,12 @@ struct StepState {
     bool alive() const { return st == TP_OK || st == TP_E_NOT_CONVERGED; }
     bool penalized() const { return o.area_penalty > 0.0 || o.volume_penalty > 0.0; }
     bool obstacle() const { return P->obs_w > 0.0 && P->obs_n > 0; }
+    bool implicit() const { return P->imp.n > 0; }
+    // weighted mesh-obstacle and implicit potentials from the fetched slots
+    double extra(const double* hs) const
+    {
+        return (obstacle() ? P->obs_w * hs[kSlotObs] : 0.0) + (implicit() ? hs[kSlotImp] : 0.0);
+    }
     // w_A (A / A0 - 1)^2 + w_V (V / V0 - 1)^2 (Sec. 7.2), A and V the total area and volume
     double penalty(double area, double vol) const
     {
@@ -1923,7 +1942,8 @@ tp_status step_group(std::vector<StepState*>& G)
         for (StepState* S : G) {
             if (S->penalized()) TP_TRY(enqueue_area_volume(S->P, S->P->V.p));   // face data describes V
             if (S->obstacle()) TP_TRY(enqueue_obstacle(S->P));
-            if (S->penalized() || S->obstacle()) BP.push_back(S->P);
+            if (S->implicit()) TP_TRY(enqueue_implicit(S->P));
+            if (S->penalized() || S->obstacle() || S->implicit()) BP.push_back(S->P);
         }
         if (!BP.empty()) {
             TP_TRY(enqueue_fetch(BP));
@@ -1939,6 +1959,14 @@ tp_status step_group(std::vector<StepState*>& G)
                 TP_HIP(launch_grad_gather(P->V.p, P->F.p, n, P->nF, P->vf_off.p, P->vf_idx.p, P->obs_g.p, P->nF,
                                           P->Vt.p, s));
                 TP_HIP(launch_axpy_block3(n, P->gbuf.p, 3, 1.0, P->Vt.p, 3, 1, &w, &c0, P->gbuf.p, 3, s));
+            }
+            if (S->implicit()) {   // the implicit potentials (weights applied in the kernel)
+                const double one = 1.0;
+                const int c0 = 0;
+                S->pen0 += P->hs.p[kSlotImp];
+                TP_HIP(launch_grad_gather(P->V.p, P->F.p, n, P->nF, P->vf_off.p, P->vf_idx.p, P->imp_g.p, P->nF,
+                                          P->Vt.p, s));
+                TP_HIP(launch_axpy_block3(n, P->gbuf.p, 3, 1.0, P->Vt.p, 3, 1, &one, &c0, P->gbuf.p, 3, s));
             }
             if (!S->penalized()) continue;
             const double area = P->hs.p[kSlotArea], vol = P->hs.p[kSlotVol6] / 6.0;
@@ -2133,6 +2161,7 @@ tp_status step_group(std::vector<StepState*>& G)
             P->geom_valid = false;
             if (S->penalized()) TP_TRY(enqueue_area_volume(P, P->Vt.p));
             if (S->obstacle()) TP_TRY(enqueue_obstacle(P));
+            if (S->implicit()) TP_TRY(enqueue_implicit(P));
             BS.push_back(P);
         }
         TP_TRY(enqueue_energy(BS, kSlotE));
@@ -2147,7 +2176,7 @@ tp_status step_group(std::vector<StepState*>& G)
                 continue;
             }
             const double Et = P->hs.p[kSlotE] + (S->penalized() ? S->penalty(P->hs.p[kSlotArea], P->hs.p[kSlotVol6] / 6.0) : 0.0) +
-                              (S->obstacle() ? P->obs_w * P->hs.p[kSlotObs] : 0.0);
+                              S->extra(P->hs.p);
             const bool valid = gs == TP_OK && finite(Et);
             const bool ok = valid && (!S->o.line_search || Et <= S->E0 + S->o.armijo_c * S->tau * S->R.slope);
             if (ok || !S->o.line_search) {
@@ -2203,6 +2232,7 @@ tp_status step_group(std::vector<StepState*>& G)
         ++P->geom_ver;
         TP_TRY(enqueue_area_volume(P, P->V.p));
         if (S->obstacle()) TP_TRY(enqueue_obstacle(P));
+        if (S->implicit()) TP_TRY(enqueue_implicit(P));
         BF.push_back(P);
         fin.push_back(S);
     }
@@ -2222,7 +2252,7 @@ tp_status step_group(std::vector<StepState*>& G)
         P->geom_valid = true;
         constraint_values(*S, P->hs.p, S->R.phi_after);
         S->R.E_new = P->hs.p[kSlotE] + S->penalty(P->hs.p[kSlotArea], P->hs.p[kSlotVol6] / 6.0) +
-                     (S->obstacle() ? P->obs_w * P->hs.p[kSlotObs] : 0.0);
+                     S->extra(P->hs.p);
     }
     // timings of the group (shared by its problems)
     const double t[8] = {tm.ms(0, 1), tm.ms(1, 2), tm.ms(1, 4), tm.ms(4, 5),
@@ -2530,6 +2560,59 @@ tp_status tp_problem_set_obstacle(tp_problem* P, const double* Vo, int64_t nVo, 
     P->obs_n = nFo;
     P->obs_p = p;
     P->obs_w = weight;
+    return TP_OK;
+}
+
+tp_status tp_problem_add_implicit(tp_problem* P, int kind, const double* q, double c, double p, double weight,
+                                  int attract)
+{
+    TP_TRY(bind(P));
+    set_error("");
+    if (kind < 0) {   // remove every implicit potential
+        P->imp.n = 0;
+        return TP_OK;
+    }
+    if (P->imp.n >= kMaxImplicit) return fail(TP_E_INVALID_ARGUMENT, "at most 8 implicit potentials");
+    if ((kind != 0 && kind != 1) || !q || !(p > 0.0) || !(weight > 0.0) || (attract != 0 && attract != 1) ||
+        !std::isfinite(c) || !std::isfinite(p) || !std::isfinite(weight))
+        return fail(TP_E_INVALID_ARGUMENT, "implicit potential: kind 0 or 1, q non-NULL, p > 0, weight > 0");
+    double qq[3] = {q[0], q[1], q[2]};
+    if (kind == 0) {
+        const double nn = std::sqrt(qq[0] * qq[0] + qq[1] * qq[1] + qq[2] * qq[2]);
+        if (!(nn > 0.0)) return fail(TP_E_INVALID_ARGUMENT, "plane normal is zero");
+        for (double& v : qq) v /= nn;
+        c /= nn;
+    } else if (!(c > 0.0)) {
+        return fail(TP_E_INVALID_ARGUMENT, "sphere radius must be > 0");
+    }
+    const int k = P->imp.n;
+    P->imp.kind[k] = kind;
+    P->imp.attract[k] = attract;
+    for (int m = 0; m < 3; ++m) P->imp.q[k][m] = qq[m];
+    P->imp.c[k] = c;
+    P->imp.p[k] = p;
+    P->imp.w[k] = weight;
+    P->imp.n = k + 1;
+    return TP_OK;
+}
+
+tp_status tp_problem_implicit_energy(tp_problem* P, double* E_out, double* dE_out)
+{
+    TP_TRY(bind(P));
+    if (!E_out) return fail(TP_E_INVALID_ARGUMENT, "E_out is NULL");
+    if (P->imp.n < 1) return fail(TP_E_INVALID_ARGUMENT, "no implicit potential is set");
+    set_error("");
+    TP_TRY(ensure_geometry(P));
+    TP_TRY(ensure_vf(P));
+    const Batch B{P};
+    TP_TRY(enqueue_implicit(P));
+    if (dE_out)
+        TP_HIP(launch_grad_gather(P->V.p, P->F.p, P->nV, P->nF, P->vf_off.p, P->vf_idx.p, P->imp_g.p, P->nF, dE_out,
+                                  P->stream));
+    TP_TRY(enqueue_fetch(B));
+    TP_TRY(sync_batch(B));
+    *E_out = P->hs.p[kSlotImp];
+    if (!std::isfinite(*E_out)) return fail(TP_E_NONFINITE, "non-finite implicit potential (a face inside an obstacle?)");
     return TP_OK;
 }
 

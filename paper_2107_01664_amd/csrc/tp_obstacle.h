@@ -17,6 +17,25 @@ hipError_t launch_obstacle_faces(const double* Vo, const int32_t* Fo, int64_t nF
 hipError_t launch_obstacle_pairs(const double4* dx, int64_t nF, const double4* xo, int64_t cap_o, double p,
                                  double* e, double* g, int64_t gs, hipStream_t s);
 
+// Implicit obstacles and attractors (Sec. 7.2) on analytic signed distances: kind 0 a plane,
+// d(x) = n . x - c (q = n, c), kind 1 a sphere, d(x) = |x - q| - c.  The potential of one
+// primitive is d^-p (obstacle) or |d|^p (attractor), weighted, evaluated at the face
+// barycenters and integrated with the face areas.
+constexpr int kMaxImplicit = 8;
+struct ImplicitSet {
+    int n = 0;
+    int kind[kMaxImplicit];
+    int attract[kMaxImplicit];
+    double q[kMaxImplicit][3];
+    double c[kMaxImplicit];
+    double p[kMaxImplicit];
+    double w[kMaxImplicit];
+};
+// Per surface face: e[T] = a_T sum_k w_k phi_k(X_T) and the face partials g = [7][gs] as for
+// launch_obstacle_pairs.
+hipError_t launch_implicit(const double4* dx, int64_t nF, const ImplicitSet& set, double* e, double* g, int64_t gs,
+                           hipStream_t s);
+
 // Vertex areas a(v) = sum of a_S / 3 over the faces S around v (dx: FP64 face data).
 hipError_t launch_vertex_area(int64_t nV, const int32_t* vf_off, const int32_t* vf_idx, const double4* dx,
                               double* out, hipStream_t s);

@@ -67,6 +67,49 @@ __global__ __launch_bounds__(kBlock) void k_obs_pairs(const double4* __restrict_
     g[6 * gs + T] = phi;
 }
 
+__global__ void k_implicit(const double4* __restrict__ dx, int64_t nF, ImplicitSet set, double* __restrict__ e,
+                           double* __restrict__ g, int64_t gs)
+{
+    const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (T >= nF) return;
+    const double4 x = dx[T];
+    double phi = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    for (int k = 0; k < set.n; ++k) {
+        double d, n0, n1, n2;   // signed distance and its gradient
+        if (set.kind[k] == 0) {
+            n0 = set.q[k][0]; n1 = set.q[k][1]; n2 = set.q[k][2];
+            d = n0 * x.x + n1 * x.y + n2 * x.z - set.c[k];
+        } else {
+            const double r0 = x.x - set.q[k][0], r1 = x.y - set.q[k][1], r2 = x.z - set.q[k][2];
+            const double r = sqrt(r0 * r0 + r1 * r1 + r2 * r2);
+            n0 = r0 / r; n1 = r1 / r; n2 = r2 / r;
+            d = r - set.c[k];
+        }
+        const double p = set.p[k], w = set.w[k];
+        double f, df;   // potential and its derivative in d
+        if (set.attract[k]) {
+            const double ad = fabs(d);
+            f = pow(ad, p);
+            df = ad > 0.0 ? p * f / d : 0.0;
+        } else {
+            f = pow(d, -p);          // NaN inside the obstacle (d < 0): the step rejects it
+            df = -p * f / d;
+        }
+        phi += w * f;
+        g0 += w * df * n0;
+        g1 += w * df * n1;
+        g2 += w * df * n2;
+    }
+    e[T] = x.w * phi;
+    g[T] = x.w * g0;
+    g[gs + T] = x.w * g1;
+    g[2 * gs + T] = x.w * g2;
+    g[3 * gs + T] = 0.0;
+    g[4 * gs + T] = 0.0;
+    g[5 * gs + T] = 0.0;
+    g[6 * gs + T] = phi;
+}
+
 __global__ void k_vertex_area(int64_t nV, const int32_t* __restrict__ vf_off, const int32_t* __restrict__ vf_idx,
                               const double4* __restrict__ dx, double* __restrict__ out)
 {
@@ -86,6 +129,14 @@ __global__ void k_add_translation(double* __restrict__ x, const int32_t* __restr
 }
 
 }  // namespace
+
+hipError_t launch_implicit(const double4* dx, int64_t nF, const ImplicitSet& set, double* e, double* g, int64_t gs,
+                           hipStream_t s)
+{
+    if (set.n < 1 || set.n > kMaxImplicit || gs < nF) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_implicit, dim3(nblk(nF)), dim3(256), 0, s, dx, nF, set, e, g, gs);
+    return hipGetLastError();
+}
 
 hipError_t launch_vertex_area(int64_t nV, const int32_t* vf_off, const int32_t* vf_idx, const double4* dx,
                               double* out, hipStream_t s)

@@ -35,6 +35,7 @@ EXPORTED = [
     "tp_problem_get_vertices", "tp_problem_energy", "tp_problem_gradient",
     "tp_problem_fractional_apply", "tp_sobolev_apply", "tp_problem_sobolev_apply",
     "tp_problem_sobolev_solve", "tp_problem_set_obstacle", "tp_problem_obstacle_energy",
+    "tp_problem_add_implicit", "tp_problem_implicit_energy",
     "tp_problem_precond_apply", "tp_step_opts_default",
     "tp_precond_step", "tp_last_error", "tp_profile_enable", "tp_profile_reset", "tp_profile_get",
     "tp_problem_poisson_solve", "tp_batch_step", "tp_problem_device_bytes",
@@ -125,6 +126,8 @@ def lib() -> ctypes.CDLL:
         "tp_problem_sobolev_apply": [vp, vp, i32, vp],
         "tp_problem_set_obstacle": [vp, vp, i64, vp, i64, ctypes.c_double, ctypes.c_double],
         "tp_problem_obstacle_energy": [vp, P(d), vp],
+        "tp_problem_add_implicit": [vp, i32, P(d), d, d, d, i32],
+        "tp_problem_implicit_energy": [vp, P(d), vp],
         "tp_problem_sobolev_solve": [vp, vp, i32, ctypes.c_double, i32, i32, i32, vp, P(GmresReport)],
         "tp_problem_precond_apply": [vp, vp, i32, vp, P(SolveReport)],
         "tp_problem_poisson_solve": [vp, vp, i32, vp, P(SolveReport)],
@@ -344,6 +347,20 @@ class Problem:
         Vo, Fo = _mesh(Vo, Fo)
         _check(lib().tp_problem_set_obstacle(self._h, Vo.data_ptr(), Vo.shape[0], Fo.data_ptr(), Fo.shape[0],
                                              p, weight))
+
+    def add_implicit(self, kind: int, q, c: float, p: float = 6.0, weight: float = 1.0, attract: bool = False):
+        """kind 0: plane q . x = c; kind 1: sphere |x - q| = c; obstacle or attractor."""
+        qa = (ctypes.c_double * 3)(*[float(v) for v in q])
+        _check(lib().tp_problem_add_implicit(self._h, kind, qa, c, p, weight, 1 if attract else 0))
+
+    def clear_implicit(self):
+        _check(lib().tp_problem_add_implicit(self._h, -1, None, 0.0, 0.0, 0.0, 0))
+
+    def implicit_energy(self, out=None):
+        dE = out if out is not None else torch.empty((self.nV, 3), dtype=torch.float64, device=self.device)
+        E = ctypes.c_double()
+        _check(lib().tp_problem_implicit_energy(self._h, ctypes.byref(E), dE.data_ptr()))
+        return E.value, dE
 
     def obstacle_energy(self, out=None):
         dE = out if out is not None else torch.empty((self.nV, 3), dtype=torch.float64, device=self.device)

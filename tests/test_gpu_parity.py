@@ -795,3 +795,47 @@ def test_step_barycenter_motion(tp, meshes):
     assert rel(x, ref.direction) <= 1e-4, rel(x, ref.direction)
     assert rel(Vn - m.V, ref.V - m.V) <= 1e-4
     assert abs(rep.slope - float(np.vdot(O.gradient(m.V, m.F)[1], ref.direction))) <= 1e-4 * abs(rep.slope)
+
+
+IMPLICIT = [dict(kind=0, q=[0.0, 0.2, 1.0], c=-2.0, p=6.0, w=0.5, attract=False),
+            dict(kind=1, q=[0.1, -0.2, 0.3], c=3.0, p=2.0, w=0.3, attract=True)]
+
+
+def _add_implicit(P, prims):
+    for pr in prims:
+        P.add_implicit(pr["kind"], pr["q"], pr["c"], p=pr["p"], weight=pr["w"], attract=pr["attract"])
+
+
+def test_implicit_energy(tp, meshes):
+    """Implicit plane obstacle and sphere attractor against the oracle (FP64)."""
+    m = meshes["small_sphere"]
+    print("[parity] implicit potentials", flush=True)
+    E0, g0 = O.implicit_potential(m.V, m.F, IMPLICIT)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        _add_implicit(P, IMPLICIT)
+        E1, g1 = P.implicit_energy()
+        with pytest.raises(tp.TpError):
+            P.add_implicit(1, [0, 0, 0], -1.0)     # radius must be positive
+    assert abs(E1 - E0) <= 1e-12 * abs(E0), (E1, E0)
+    assert rel(g1.cpu().numpy(), g0) <= 1e-11
+
+
+def test_step_implicit(tp, meshes):
+    """A step with the implicit potentials and both hard constraints, fixed tau, against the
+    oracle's step."""
+    m = meshes["small_sphere"]
+    print("[parity] step with implicit potentials", flush=True)
+    tau = 2e-3
+    ref = O.precond_step(m.V, m.F, tau=tau, line_search=False, implicit=IMPLICIT)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        _add_implicit(P, IMPLICIT)
+        d = torch.empty((m.nV, 3), dtype=torch.float64, device="cuda")
+        rep = P.step(tp.step_opts(tau0=tau, line_search=0), direction=d)
+        Vn = P.vertices().cpu().numpy()
+    x = d.cpu().numpy()
+    print("  direction error", rel(x, ref.direction), flush=True)
+    assert rel(x, ref.direction) <= 1e-4, rel(x, ref.direction)
+    assert rel(Vn - m.V, ref.V - m.V) <= 1e-4
+    assert abs(rep.E - ref.E) <= TOL32 * ref.E
+    E_new = O.energy(Vn, m.F) + O.implicit_potential(Vn, m.F, IMPLICIT, False)[0]
+    assert abs(rep.E_new - E_new) <= TOL32 * E_new

@@ -586,3 +586,32 @@ def test_barycenter_motion():
         idx = labels == lab
         t = -(av[idx] @ g[idx]) / av[idx].sum()
         assert np.abs(x1[idx] - x0[idx] - t).max() <= 1e-12 * np.abs(x0).max()
+
+
+PRIMS = [dict(kind=0, q=[0.0, 0.2, 1.0], c=-2.0, p=6.0, w=0.5, attract=False),
+         dict(kind=1, q=[0.1, -0.2, 0.3], c=3.0, p=2.0, w=0.3, attract=True)]
+
+
+def test_implicit_potential(noisy2):
+    """Implicit obstacle (plane below the mesh) and attractor (sphere around it) of Sec. 7.2:
+    differential against central differences; a plane through the origin and a sphere about
+    the origin scale as lambda^(2 -+ p) with the mesh; far plane: E -> w total_area d^-p."""
+    V, F = noisy2.V, noisy2.F
+    E, g = O.implicit_potential(V, F, PRIMS)
+    rng = np.random.default_rng(12)
+    for _ in range(3):
+        d = rng.standard_normal(V.shape)
+        h = 1e-6
+        fd = (O.implicit_potential(V + h * d, F, PRIMS, False)[0] - O.implicit_potential(V - h * d, F, PRIMS, False)[0]) / (2 * h)
+        assert abs(fd - np.vdot(g, d)) <= 1e-6 * abs(fd), (fd, np.vdot(g, d))
+    Vs = V + np.array([0.0, 0.0, 4.0])
+    ob = [dict(kind=0, q=[0, 0, 1], c=0.0, p=6.0, w=1.0)]
+    at = [dict(kind=1, q=[0, 0, 0], c=0.5, p=2.0, w=1.0, attract=True)]
+    for prim, expo in ((ob, 2 - 6.0), (at, 2 + 2.0)):
+        e1 = O.implicit_potential(Vs, F, prim, False)[0]
+        e2 = O.implicit_potential(1.8 * Vs, F, [dict(pr, c=1.8 * pr["c"]) for pr in prim], False)[0]
+        assert abs(e2 - 1.8 ** expo * e1) <= 1e-12 * abs(e2)
+    Ef = O.implicit_potential(V, F, [dict(kind=0, q=[0, 0, 1], c=-1000.0, p=6.0, w=1.0)], False)[0]
+    # heights within 1 of the plane's offset 1000: the relative deviation is O(6 z / 1000)
+    # to first order (mean z near 0 here), so 1e-4
+    assert abs(Ef - O.total_area(V, F) * 1000.0 ** -6) <= 1e-4 * Ef
