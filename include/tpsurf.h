@@ -213,7 +213,7 @@ typedef struct {
 } tp_gmres_report;
 
 /* x = A^+ P b columnwise, A = B + B0 as in tp_sobolev_apply: the solve of the descent step
- * done with the true operator (Sec. 5.4, step 3: an iterative method with the preconditioner
+ * done with the true operator (Sec. 5.4: an iterative method with the preconditioner
  * of Sec. 5.2 and a zero initial guess; products with A evaluated directly rather than with
  * the block cluster tree).  A annihilates the global constants only: its low-order term
  * couples the connected components.  P subtracts the global mean and x has global mean
@@ -264,7 +264,7 @@ typedef struct {
     double area_target;      /* NaN selects the area of the mesh at tp_problem_create    */
     double volume_target;    /* NaN selects the volume at tp_problem_create              */
     int    solver;           /* 0 (default): the direction with A~^{-1} in place of A_3^{-1};
-                                1: A_3^{-1} by GMRES on A = B + B0 (Sec. 5.4, step 3;
+                                1: A_3^{-1} by GMRES on A = B + B0 (Sec. 5.4;
                                 tp_problem_sobolev_solve with the diagonal term)           */
     double solver_rtol;      /* GMRES relative residual, default 1e-4 (solver = 1); with
                                 FP32 pair terms the attainable residual of smooth

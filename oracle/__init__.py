@@ -484,7 +484,7 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
                  volume_penalty=0.0, obstacle_mesh=None, obstacle_p=6.0, obstacle_weight=0.0,
                  barycenter_motion=False, implicit=None):
     """One constrained descent step with A~^{-1} in place of A_3^{-1}, or with the map R -> Y
-    given as `inverse` (for instance A_3^{-1} from dense_sobolev_inverse; Sec. 5.4, step 3).
+    given as `inverse` (for instance A_3^{-1} from dense_sobolev_inverse; Sec. 5.4).
 
     1. g = dE (Sec. 3.1).  2. J = rows of the active constraints: total area (Sec. 7.1.3)
     and total volume (Sec. 7.1.4).  3. Y = A~^{-1} J^T, y_g = A~^{-1} g; Schur matrix

@@ -1344,7 +1344,7 @@ tp_status run_sobolev(tp_problem* P, const double* u, int ldu, int k, double* Au
 }
 
 // x = A^+ P b columnwise by right-preconditioned GMRES(m) on A = B + B0 with the
-// preconditioner A~^{-1} of Sec. 5.2 and a zero initial guess (Sec. 5.4, step 3a).  The
+// preconditioner A~^{-1} of Sec. 5.2 and a zero initial guess (Sec. 5.4).  The
 // preconditioner is applied through CG solves, so the directions it returns are kept (Z)
 // and the solution is formed from them (the flexible form of GMRES).  The k columns run in
 // lockstep, each with its own Krylov space, Hessenberg matrix and stopping test; classical
@@ -2001,7 +2001,7 @@ tp_status step_group(std::vector<StepState*>& G)
         }
     }
     // 3. Y = A~^{-1} R (shared all-pairs and CG launches), or with solver = 1 Y = A^+ R by
-    //    GMRES on the true operator, one problem at a time (Sec. 5.4, step 3)
+    //    GMRES on the true operator, one problem at a time (Sec. 5.4)
     tm.mark(1);
     const bool gmres = G[0]->o.solver == 1;
     std::vector<tp_gmres_report> grep(G.size());
