@@ -307,7 +307,7 @@ typedef struct {
                                 [7] number of problems whose launches this step shared    */
 } tp_step_report;
 
-/* One projected, preconditioned descent step (Sec. 3 steps 1-5 with Sec. 5.3-5.4):
+/* One projected, preconditioned descent step (the basic step of Sec. 3 with Sec. 5.3-5.4):
  * g = dE; J = active constraint rows; Y = A~^{-1} J^T, y_g = A~^{-1} g (one 3(1+k)-column
  * preconditioner application); S = J Y; x = -(y_g - Y S^{-1} J y_g); Armijo on E(f + tau x);
  * f <- f + tau x - Y S^{-1} Phi(f + tau x).  The problem's vertices are updated.
