@@ -335,7 +335,10 @@ TP_API tp_status tp_problem_device_bytes(const tp_problem* prob, uint64_t* bytes
 /* Upper bound of the device memory a problem with nV vertices, nF faces, largest vertex
  * degree max_degree and ncomp connected components holds after descent steps with
  * n_constraints (0..2) active constraint rows, for admission against a memory budget.
- * Uses the current device's pair-kernel plans. */
+ * Uses the current device's pair-kernel plans.  Covers the default step (solver 0); the
+ * GMRES solve (2 (restart + 1) nV k doubles of Krylov vectors and its work arrays), an
+ * obstacle (32 B per obstacle face, 64 B per surface face) and barycenter motions (8 B
+ * per vertex) come on top. */
 TP_API tp_status tp_estimate_device_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp,
                                           const tp_params* params, int n_constraints,
                                           uint64_t* bytes);
