@@ -13,7 +13,7 @@
  *     solves done by FP64 conjugate gradients on the cotan stiffness matrix C;
  *   - one projected descent step with total-area and total-volume constraints (Sec. 3,
  *     eq. SaddleProblem via the Schur complement of Sec. 5.3, Armijo line search, and the
- *     corrective projection of Sec. 5.4.1), A~^{-1} standing in for A_3^{-1}.
+ *     corrective projection of Sec. 5.3.1), A~^{-1} standing in for A_3^{-1}.
  *
  * Conventions shared by every entry point
  *   - V: vertex positions, nV x 3, row-major double.  F: faces, nF x 3, row-major int32,
@@ -119,9 +119,9 @@ TP_API tp_status tp_fractional_apply(const double* V, int64_t nV, const int32_t*
                               const tp_params* params, const double* u, int k,
                               double* Lu_out, void* stream);
 
-/* Au = A u = (B + B0) u for k columns: the operator of the paper's inner product (Sec. 2.3,
+/* Au = A u = (B + B0) u for k columns: the operator of the paper's inner product (Sec. 2.4,
  * high- and low-order terms; discrete forms eqs. DiscreteHighOrderTerm and
- * DiscreteLowOrderTerm of Sec. 3.3), applied in the factored form of Sec. 5.1.2 / 5.1.3:
+ * DiscreteLowOrderTerm of Sec. 3.2.1), applied in the factored form of Sec. 5.1.2 / 5.1.3:
  *   B u  = 2 (diag(a) D)^T [diag(diag(a)^-1 H a) - H] diag(a) D u,  H_ST = (1 - delta_ST)|X_S - X_T|^-2s,
  *   B0 u = 2 U^T [diag(diag(a)^-1 H0 a) - H0] U u,  H0_ST = H_ST (K2(S,T) + K2(T,S)) / 2,
  * with s = (beta - 2) / alpha (sigma = s - 1 in the paper's notation for these terms),
@@ -174,7 +174,7 @@ TP_API tp_status tp_problem_gradient(tp_problem* prob, double* E_out, double* dE
 TP_API tp_status tp_problem_fractional_apply(tp_problem* prob, const double* u, int k, double* Lu_out);
 TP_API tp_status tp_problem_sobolev_apply(tp_problem* prob, const double* u, int k, double* Au_out);
 
-/* Static obstacle (Sec. 7.2): a fixed mesh (Vo: nVo x 3 double, Fo: nFo x 3 int32, device,
+/* Static obstacle (Sec. 7.3.2): a fixed mesh (Vo: nVo x 3 double, Fo: nFo x 3 int32, device,
  * copied at the call) that repels the surface with the potential
  *   E_obs = sum_T a_T sum_{S in obstacle} a_O(S) |X_O(S) - X_T|^-p
  * (the obstacle potential of the paper evaluated at the barycenter of every face T of the
@@ -188,10 +188,12 @@ TP_API tp_status tp_problem_set_obstacle(tp_problem* prob, const double* Vo, int
  * differential with respect to the surface's vertex positions. */
 TP_API tp_status tp_problem_obstacle_energy(tp_problem* prob, double* E_out, double* dE_out);
 
-/* Implicit obstacles and attractors (Sec. 7.2) on analytic signed distances d: kind 0 a
+/* Implicit obstacles and attractors (Sec. 7.3.3) on analytic signed distances d: kind 0 a
  * plane, d(x) = (q . x - c) / |q|; kind 1 a sphere, d(x) = |x - q| - c (c > 0 the radius;
  * q: host pointer to 3 doubles).  Potential weight * d^-p for an obstacle (attract = 0; a
- * face barycenter with d <= 0 makes it non-finite, and the line search rejects such steps),
+ * face barycenter with d <= 0 makes it +infinity for every p, and the line search rejects
+ * such steps; a step whose corrected positions put a barycenter there ends with
+ * TP_E_NONFINITE),
  * weight * |d|^p for an attractor (attract = 1), evaluated at the face barycenters and
  * integrated with the face areas, summed over the primitives (at most 8) and added to the
  * objective of every later step.  kind < 0 removes them all.  TP_E_INVALID_ARGUMENT for a
@@ -270,13 +272,15 @@ typedef struct {
                                 FP32 pair terms the attainable residual of smooth
                                 right-hand sides (the constraint rows) lies near 1e-6     */
     int    solver_maxiter;   /* GMRES iterations at most, default 300 (solver = 1)        */
-    double area_penalty;     /* w_A >= 0 of the potential w_A (A / A_0 - 1)^2 (Sec. 7.2),
+    double area_penalty;     /* w_A >= 0 of the potential w_A (A / A_0 - 1)^2 (Sec. 7.3.1),
                                 A_0 = area_target; default 0                              */
     double volume_penalty;   /* w_V >= 0 of w_V (V / V_0 - 1)^2, V_0 = volume_target;
                                 default 0.  With either weight > 0 the step minimises
                                 the tangent-point energy plus the potentials: their
                                 gradients join dE, the line search and E / E_new of the
-                                report include them                                       */
+                                report include them.  A weight > 0 with a target (or,
+                                for a NaN target, an initial measure) of 0 gives
+                                TP_E_INVALID_ARGUMENT: the potential divides by it       */
     int    barycenter_motion; /* 1: barycenter motions (Sec. 7.1.1): the solve removes every
                                 component's mean, and the translation by minus the
                                 vertex-area-weighted mean of dE (of the total objective)

@@ -230,7 +230,7 @@ def dense_fractional_matrix(V, F, sigma):
 
 
 # ----------------------------------------------------------------------------------
-# The inner-product operator A = B + B0 (Sec. 2.3; discrete terms in Sec. 3.3; applied in
+# The inner-product operator A = B + B0 (Sec. 2.4; discrete terms in Sec. 3.2.1; applied in
 # the factored form of Sec. 5.1.2 and 5.1.3).  Its kernel exponent is 2s (sigma = s - 1).
 
 def face_gradients(V, F, u):
@@ -302,7 +302,7 @@ def dense_sobolev_matrices(V, F, s):
     """|V| x |V| matrices B and B0 assembled pair by pair from eqs. DiscreteHighOrderTerm and
     DiscreteLowOrderTerm (tiny meshes only), over all ordered pairs S != T.
 
-    D phi_i(S) is taken from its definition d phi_i (df)^+ (Sec. 2.3): df is the 3 x 2
+    D phi_i(S) is taken from its definition d phi_i (df)^+ (Sec. 2.4): df is the 3 x 2
     Jacobian of the affine map from the unit triangle onto S, and ^+ its Moore-Penrose
     pseudoinverse (numpy.linalg.pinv).  K2(S,T) = |N_S . (X_S - X_T)|^2 / |X_S - X_T|^4 is
     used as written, not symmetrized."""
@@ -494,8 +494,8 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     4. Armijo backtracking from tau0 (constants c = 1e-4, shrink 1/2, at most 30 halvings;
     the paper names the rule but not the constants).  tau0 defaults to the step whose
     largest vertex move is half the mean edge length.  With line_search=False, tau = tau0.
-    5. Corrective step h = -Y S^{-1} Phi(f + tau x) (Sec. 5.4.1), added to f + tau x.
-    With area_penalty / volume_penalty > 0 the objective is E plus the potentials of Sec. 7.2
+    5. Corrective step h = -Y S^{-1} Phi(f + tau x) (Sec. 5.3.1), added to f + tau x.
+    With area_penalty / volume_penalty > 0 the objective is E plus the potentials of Sec. 7.3.1
     (penalty_terms): their gradients join g and the line search, and E of the result is the
     total.  obstacle_mesh = (Vo, Fo) with obstacle_weight > 0 adds weight x the obstacle
     potential (obstacle) to the objective in the same way.  barycenter_motion adds to x, per
@@ -565,10 +565,13 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     t = tau0
     bt = 0
     if line_search:
-        while objective(V + t * x) > E0 + ARMIJO_C * t * slope and bt < ARMIJO_MAX_BACKTRACKS:
+        # a non-finite objective fails the test (written so that NaN is not accepted)
+        while not (objective(V + t * x) <= E0 + ARMIJO_C * t * slope) and bt < ARMIJO_MAX_BACKTRACKS:
             t *= ARMIJO_SHRINK
             bt += 1
     Vt = V + t * x
+    if line_search and not np.isfinite(objective(Vt)):
+        raise FloatingPointError("line search found no step with a finite objective")
     if k:
         phi = np.array([fns[m](Vt, F) - targets[m] for m in range(k)])
         lam = np.linalg.solve(S, phi)
@@ -583,7 +586,7 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
 
 
 def obstacle(V, F, Vo, Fo, p=6.0, with_grad=True):
-    """Static obstacle potential of Sec. 7.2 at the surface's face barycenters, integrated over
+    """Static obstacle potential of Sec. 7.3.2 at the surface's face barycenters, integrated over
     the faces, and its differential with respect to the surface vertices (tpo_obstacle)."""
     V, F = _prep(V, F)
     Vo, Fo = _prep(Vo, Fo)
@@ -594,7 +597,7 @@ def obstacle(V, F, Vo, Fo, p=6.0, with_grad=True):
 
 
 def implicit_potential(V, F, prims, with_grad=True):
-    """Implicit obstacles and attractors of Sec. 7.2, evaluated at the face barycenters and
+    """Implicit obstacles and attractors of Sec. 7.3.3, evaluated at the face barycenters and
     integrated with the face areas: sum_k w_k sum_T a_T phi_k(X_T), phi = d^-p (obstacle) or
     |d|^p (attractor); d the signed distance to a plane {x : q.x = c} (kind 0, q normalised
     with c) or a sphere of center q and radius c (kind 1).  prims: list of dicts with keys
@@ -620,8 +623,12 @@ def implicit_potential(V, F, prims, with_grad=True):
             f = np.abs(d) ** p
             df = p * np.abs(d) ** (p - 1.0) * np.sign(d)
         else:
-            f = d ** (-p)
-            df = -p * d ** (-p - 1.0)
+            # on or inside the obstacle the potential is +infinity for every p (d^-p alone
+            # would be finite for an even p and negative for an odd one when d < 0)
+            inside = d <= 0.0
+            ds = np.where(inside, 1.0, d)
+            f = np.where(inside, np.inf, ds ** (-p))
+            df = np.where(inside, -np.inf, -p * ds ** (-p - 1.0))
         phi += w * f
         dphi += (w * df)[:, None] * n
     E = float(np.sum(a * phi))
@@ -636,7 +643,7 @@ def implicit_potential(V, F, prims, with_grad=True):
 
 
 def penalty_terms(V, F, A0, V0, area_weight, volume_weight):
-    """Total area and volume potentials of Sec. 7.2, w_A (A/A0 - 1)^2 + w_V (V/V0 - 1)^2, and
+    """Total area and volume potentials of Sec. 7.3.1, w_A (A/A0 - 1)^2 + w_V (V/V0 - 1)^2, and
     their gradient with respect to the vertex positions (nV x 3)."""
     A, Vol = total_area(V, F), total_volume(V, F)
     e = area_weight * (A / A0 - 1.0) ** 2 + volume_weight * (Vol / V0 - 1.0) ** 2

@@ -347,8 +347,8 @@ EXPORT int tpo_fractional_apply(const double* V, int64_t nV, const int32_t* F, i
 }
 
 /* ------------------------------------------------------------------------- */
-/* The operator A = B + B0 of the inner product (Sec. 2.3, the high- and low-order terms;
- * discretized in Sec. 3.3, eqs. DiscreteHighOrderTerm and DiscreteLowOrderTerm) applied to
+/* The operator A = B + B0 of the inner product (Sec. 2.4, the high- and low-order terms;
+ * discretized in Sec. 3.2.1, eqs. DiscreteHighOrderTerm and DiscreteLowOrderTerm) applied to
  * k columns, with sigma = s - 1 so that |d|^-(2 sigma + 2) = |d|^-2s:
  *
  *   (B u)_i  = sum_{S != T} < D phi_i(S) - D phi_i(T), D u(S) - D u(T) > |d|^-2s a_S a_T
@@ -487,7 +487,7 @@ EXPORT int tpo_sobolev_apply(const double* V, int64_t nV, const int32_t* F, int6
 }
 
 /* ------------------------------------------------------------------------- */
-/* Static obstacle potential (Sec. 7.2): the obstacle's potential sum_S a_O(S) |X_O(S) - x|^-p
+/* Static obstacle potential (Sec. 7.3.2): the obstacle's potential sum_S a_O(S) |X_O(S) - x|^-p
  * evaluated at the barycenter of every surface face T and integrated over T:
  *   E_obs = sum_T a_T phi(T),  phi(T) = sum_S a_O(S) |X_O(S) - X_T|^-p.
  * Its differential with respect to the surface vertices, by the chain rule through X_T

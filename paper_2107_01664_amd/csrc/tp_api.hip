@@ -257,7 +257,7 @@ struct tp_problem {
     DevBuf<double> gm_V, gm_Z, gm_w, gm_b, gm_r, gm_x, gm_small, gm_red, gm_Q, gm_Qn, gm_AQ, gm_one, gm_dinv,
         gm_sv, gm_sw, gm_smw;
     DevBuf<int32_t> gm_lab0;
-    // static obstacle (Sec. 7.2): face data of the obstacle mesh, per-face work arrays
+    // static obstacle (Sec. 7.3.2): face data of the obstacle mesh, per-face work arrays
     DevBuf<double4> obs_x;
     DevBuf<double> obs_e, obs_g, bm_area, bm_t, imp_e, imp_g;
     ImplicitSet imp;
@@ -1834,7 +1834,7 @@ struct HostSolve2 {
 // One constrained, preconditioned descent step (Sec. 3 and Sec. 5.4 with A~^{-1} in place
 // of the GMRES solve): g = dE; Y = A~^{-1}[g | J_A^T | J_V^T]; Schur system S = J Y; direction
 // x = -(y_g - Y S^{-1} J y_g); Armijo line search on E(f + tau x); corrective projection
-// f <- f + tau x - Y S^{-1} Phi(f + tau x) (Sec. 3.3, Sec. 5.3).
+// f <- f + tau x - Y S^{-1} Phi(f + tau x) (Sec. 3.3.2, Sec. 5.3.1).
 
 // Obstacle potential at the current face data into slot kSlotObs, and its face partials in
 // obs_g ([7][nF], for launch_grad_gather).
@@ -1879,7 +1879,7 @@ struct StepState {
     {
         return (obstacle() ? P->obs_w * hs[kSlotObs] : 0.0) + (implicit() ? hs[kSlotImp] : 0.0);
     }
-    // w_A (A / A0 - 1)^2 + w_V (V / V0 - 1)^2 (Sec. 7.2), A and V the total area and volume
+    // w_A (A / A0 - 1)^2 + w_V (V / V0 - 1)^2 (Sec. 7.3.1), A and V the total area and volume
     double penalty(double area, double vol) const
     {
         double e = 0.0;
@@ -1935,7 +1935,7 @@ tp_status step_group(std::vector<StepState*>& G)
         for (tp_problem* P : B) gp.push_back(P->gbuf.p);
         TP_TRY(enqueue_gradient(B, gp.data(), kSlotE));
     }
-    // 1b. penalty potentials (Sec. 7.2): their gradients are added to g,
+    // 1b. penalty potentials (Sec. 7.3.1): their gradients are added to g,
     //     2 w_A (A / A0 - 1) / A0 dA + 2 w_V (V / V0 - 1) / V0 dV
     {
         Batch BP;
@@ -2253,6 +2253,10 @@ tp_status step_group(std::vector<StepState*>& G)
         constraint_values(*S, P->hs.p, S->R.phi_after);
         S->R.E_new = P->hs.p[kSlotE] + S->penalty(P->hs.p[kSlotArea], P->hs.p[kSlotVol6] / 6.0) +
                      S->extra(P->hs.p);
+        // the corrective projection can move a barycenter into an obstacle (or onto
+        // another one) after the line search accepted the trial point
+        if (!finite(S->R.E_new))
+            S->st = fail(TP_E_NONFINITE, "the corrected positions give a non-finite energy (a face inside an obstacle?)");
     }
     // timings of the group (shared by its problems)
     const double t[8] = {tm.ms(0, 1), tm.ms(1, 2), tm.ms(1, 4), tm.ms(4, 5),
@@ -2316,6 +2320,15 @@ tp_status run_step_batch(tp_problem* const* probs, int n, const tp_step_opts* op
         }
         T.A0 = std::isnan(T.o.area_target) ? P->area0 : T.o.area_target;
         T.V0 = std::isnan(T.o.volume_target) ? P->vol0 : T.o.volume_target;
+        // the potentials divide by their targets: a zero (or non-finite) target is an
+        // argument error, not a non-finite energy later in the step
+        if ((T.o.area_penalty > 0.0 && (!std::isfinite(T.A0) || T.A0 == 0.0)) ||
+            (T.o.volume_penalty > 0.0 && (!std::isfinite(T.V0) || T.V0 == 0.0))) {
+            T.st = fail(TP_E_INVALID_ARGUMENT,
+                        "area_penalty / volume_penalty need a finite, non-zero area / volume target "
+                        "(the initial measure is used when the target is NaN)");
+            continue;
+        }
         T.kc = (T.o.constrain_area ? 1 : 0) + (T.o.constrain_volume ? 1 : 0);
         T.ncol = 3 * (1 + T.kc);
     }

@@ -1,4 +1,4 @@
-// Static obstacle potential (Sec. 7.2): a fixed mesh O repels the surface with
+// Static obstacle potential (Sec. 7.3.2): a fixed mesh O repels the surface with
 //   E_obs = sum_T a_T sum_{S in O} a_O(S) |X_O(S) - X_T|^-p,
 // the potential of every face T of the surface evaluated at its barycenter and integrated
 // over its area.
@@ -17,7 +17,7 @@ hipError_t launch_obstacle_faces(const double* Vo, const int32_t* Fo, int64_t nF
 hipError_t launch_obstacle_pairs(const double4* dx, int64_t nF, const double4* xo, int64_t cap_o, double p,
                                  double* e, double* g, int64_t gs, hipStream_t s);
 
-// Implicit obstacles and attractors (Sec. 7.2) on analytic signed distances: kind 0 a plane,
+// Implicit obstacles and attractors (Sec. 7.3.3) on analytic signed distances: kind 0 a plane,
 // d(x) = n . x - c (q = n, c), kind 1 a sphere, d(x) = |x - q| - c.  The potential of one
 // primitive is d^-p (obstacle) or |d|^p (attractor), weighted, evaluated at the face
 // barycenters and integrated with the face areas.

@@ -1,4 +1,4 @@
-// Static obstacle potential (Sec. 7.2) on the GPU, FP64 pair terms: one thread per surface
+// Static obstacle potential (Sec. 7.3.2) on the GPU, FP64 pair terms: one thread per surface
 // face T, the obstacle's faces streamed through LDS in tiles of kTileJ (every lane reads the
 // same obstacle face).  Per pair, with d = X_T - X_O(S) and r2 = |d|^2:
 //   w = a_O(S) r2^(-p/2),  phi(T) += w,  dphi/dX_T += -p w d / r2.
@@ -91,9 +91,15 @@ __global__ void k_implicit(const double4* __restrict__ dx, int64_t nF, ImplicitS
             const double ad = fabs(d);
             f = pow(ad, p);
             df = ad > 0.0 ? p * f / d : 0.0;
-        } else {
-            f = pow(d, -p);          // NaN inside the obstacle (d < 0): the step rejects it
+        } else if (d > 0.0) {
+            f = pow(d, -p);
             df = -p * f / d;
+        } else {
+            // on or inside the obstacle: the potential is infinite whatever p is (for an
+            // even integer p, pow(d, -p) would be finite on the far side of the barrier,
+            // and for an odd one negative), so the line search rejects such a step
+            f = INFINITY;
+            df = -INFINITY;
         }
         phi += w * f;
         g0 += w * df * n0;

@@ -1,4 +1,4 @@
-// The inner-product operator A = B + B0 (Sec. 2.3; discrete terms in Sec. 3.3) applied in
+// The inner-product operator A = B + B0 (Sec. 2.4; discrete terms in Sec. 3.2.1) applied in
 // the factored form of Sec. 5.1.2 and 5.1.3.
 #pragma once
 #include "tp_internal.h"

@@ -1,4 +1,4 @@
-// The inner-product operator A = B + B0 (Sec. 2.3; discrete terms in Sec. 3.3, eqs.
+// The inner-product operator A = B + B0 (Sec. 2.4; discrete terms in Sec. 3.2.1, eqs.
 // DiscreteHighOrderTerm and DiscreteLowOrderTerm), applied in the factored form of
 // Sec. 5.1.2 and 5.1.3:
 //

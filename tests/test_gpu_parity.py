@@ -734,6 +734,13 @@ def test_step_penalties(tp, meshes):
     E_new = O.energy(Vn, m.F) + O.penalty_terms(Vn, m.F, A0, V0, 5.0, 5.0)[0]
     assert abs(rep.E_new - E_new) <= TOL32 * E_new
     assert rep.slope < 0
+    # a zero target (the potential divides by it) is an argument error before any work
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        for kw in (dict(volume_target=0.0, volume_penalty=1.0), dict(area_target=0.0, area_penalty=1.0)):
+            with pytest.raises(tp.TpError) as ei:
+                P.step(tp.step_opts(constrain_area=0, constrain_volume=0, **kw))
+            assert ei.value.status == 1, ei.value
+        assert np.array_equal(P.vertices().cpu().numpy(), m.V)
 
 
 def _obstacle_mesh():
@@ -839,3 +846,23 @@ def test_step_implicit(tp, meshes):
     assert abs(rep.E - ref.E) <= TOL32 * ref.E
     E_new = O.energy(Vn, m.F) + O.implicit_potential(Vn, m.F, IMPLICIT, False)[0]
     assert abs(rep.E_new - E_new) <= TOL32 * E_new
+
+
+@pytest.mark.parametrize("p", [6.0, 3.0])
+def test_step_implicit_barrier(tp, meshes, p):
+    """A plane just below the mesh that the first Armijo trial would cross (Sec. 7.3.3): the
+    barrier is +infinity there for even and odd p, so the GPU line search halves the step
+    like the oracle's and every barycenter of the result stays above the plane."""
+    m = meshes["small_sphere"]
+    print(f"[parity] implicit barrier p={p}", flush=True)
+    zmin = O.faces(m.V, m.F)[0][:, 2].min()
+    plane = [dict(kind=0, q=[0.0, 0.0, 1.0], c=zmin - 0.02, p=p, w=1e-14, attract=False)]
+    ref = O.precond_step(m.V, m.F, constrain_area=False, constrain_volume=False, implicit=plane)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        _add_implicit(P, plane)
+        rep = P.step(tp.step_opts(constrain_area=0, constrain_volume=0))
+        Vn = P.vertices().cpu().numpy()
+    assert rep.backtracks == ref.backtracks and abs(rep.tau - ref.tau) <= 1e-6 * ref.tau
+    assert O.faces(Vn, m.F)[0][:, 2].min() > zmin - 0.02
+    assert math.isfinite(rep.E_new)
+    assert rel(Vn - m.V, ref.V - m.V) <= 1e-4

@@ -269,7 +269,7 @@ def _planar_grid(n=5):
 
 def test_face_gradients_of_linear_functions(noisy2):
     """D u of u(x) = <c, x> on a face is the part of c in the face's plane, (I - N N^T) c,
-    whatever the corner order or orientation of the face (the gradient of Sec. 2.3 read as
+    whatever the corner order or orientation of the face (the gradient of Sec. 2.4 read as
     N x e_jk / (2 a) with unnormalized opposite edges)."""
     c = np.array([[0.3, -1.2, 0.7], [2.0, 0.5, -0.1]]).T           # two linear functions
     u = noisy2.V @ c
@@ -319,7 +319,7 @@ def test_sobolev_planar_mesh():
 
 
 def test_sobolev_scaling_and_rigid(noisy2):
-    """B and B0 have the same units (the reason for K2 in Sec. 2.3): under f -> lambda f the
+    """B and B0 have the same units (the reason for K2 in Sec. 2.4): under f -> lambda f the
     whole operator scales as lambda^(2 - 2s); rigid motions leave it unchanged."""
     s = 5.0 / 3.0
     u = RNG.standard_normal((noisy2.nV, 2))
@@ -429,7 +429,7 @@ def test_step_direction_properties():
 
 def test_corrective_projection_order():
     """Along a tangent direction the constraint error is second order in tau; one Newton
-    correction with the Jacobian at f (Sec. 3.3.2, Sec. 5.4.1) leaves a third-order error.
+    correction with the Jacobian at f (Sec. 3.3.2, Sec. 5.3.1) leaves a third-order error.
     Halving tau cuts |Phi(f + tau x)| by ~4 and the corrected error by ~8."""
     m = mg.add_noise(mg.icosphere(2), 0.02, 2)
     trial, after = [], []
@@ -497,7 +497,7 @@ def test_preconditioner_spectrum_and_diagonal_term():
 
 def test_dense_sobolev_inverse_and_true_operator_step():
     """The oracle's A^+ P solves A Y = P R with global mean zero; the step built on it solves
-    the saddle-point system of Sec. 3.3 with the true operator: J x = 0 and
+    the saddle-point system of Sec. 3.3.1 with the true operator: J x = 0 and
     A x + g lies in the span of the constraint rows and the constants."""
     m = mg.add_noise(mg.icosphere(1), 0.03, 4)
     s = 5.0 / 3.0
@@ -519,7 +519,7 @@ def test_dense_sobolev_inverse_and_true_operator_step():
 
 
 def test_penalty_potentials(noisy2):
-    """The area and volume potentials of Sec. 7.2: gradient against central differences; a
+    """The area and volume potentials of Sec. 7.3.1: gradient against central differences; a
     step on them alone (no hard constraints) descends the total objective."""
     V, F = noisy2.V, noisy2.F
     A0, V0 = 0.9 * O.total_area(V, F), 1.1 * O.total_volume(V, F)
@@ -540,7 +540,7 @@ def test_penalty_potentials(noisy2):
 
 
 def test_obstacle_potential(noisy2):
-    """Obstacle potential of Sec. 7.2: differential against central differences, the scaling
+    """Obstacle potential of Sec. 7.3.2: differential against central differences, the scaling
     law E(lambda f, lambda f_O) = lambda^(4 - p) E, invariance under a rigid motion of both
     meshes, and a far obstacle seen as one point mass: E -> a_O,total sum_T a_T |X_T - c|^-p."""
     V, F = noisy2.V, noisy2.F
@@ -593,7 +593,7 @@ PRIMS = [dict(kind=0, q=[0.0, 0.2, 1.0], c=-2.0, p=6.0, w=0.5, attract=False),
 
 
 def test_implicit_potential(noisy2):
-    """Implicit obstacle (plane below the mesh) and attractor (sphere around it) of Sec. 7.2:
+    """Implicit obstacle (plane below the mesh) and attractor (sphere around it) of Sec. 7.3.3:
     differential against central differences; a plane through the origin and a sphere about
     the origin scale as lambda^(2 -+ p) with the mesh; far plane: E -> w total_area d^-p."""
     V, F = noisy2.V, noisy2.F
@@ -615,3 +615,56 @@ def test_implicit_potential(noisy2):
     # heights within 1 of the plane's offset 1000: the relative deviation is O(6 z / 1000)
     # to first order (mean z near 0 here), so 1e-4
     assert abs(Ef - O.total_area(V, F) * 1000.0 ** -6) <= 1e-4 * Ef
+
+
+# ------------------------------------------------------------- row-sampling helpers
+
+@pytest.mark.parametrize("name", ["small_sphere", "noisy_l2"])
+def test_row_sampling_helpers_match_full_sums(noisy2, name):
+    """gradient_at_vertices and fractional_at_vertices (the sampled rows that full-size GPU
+    parity compares against) equal the rows of the full, separately pinned gradient
+    (Sec. 3.1) and fractional apply (eq. DiscreteLaplacianQuartic): the sampled path runs its
+    own row list and vertex gather in C, so a wrong index, a dropped row or a missing
+    incident face shows up here.  Meshes of 320 and 1,280 faces, vertices at both ends of
+    the numbering, vertices sharing faces, and k = 1 and 3 columns."""
+    m = noisy2 if name == "noisy_l2" else mg.workload("small_sphere")
+    V, F = m.V, m.F
+    nV = V.shape[0]
+    verts = [0, 1, 2, nV // 3, nV // 2, nV // 2 + 1, nV - 2, nV - 1]
+    verts += list(F[5])                       # the three corners of one face
+    _, g = O.gradient(V, F)
+    gs = O.gradient_at_vertices(V, F, verts)
+    assert np.abs(gs - g[verts]).max() <= 1e-13 * np.abs(g).max()
+    for alpha, beta in ((4.0, 9.0),):
+        _, g2 = O.gradient(V, F, alpha, beta)
+        gs2 = O.gradient_at_vertices(V, F, verts, alpha, beta)
+        assert np.abs(gs2 - g2[verts]).max() <= 1e-13 * np.abs(g2).max()
+    sigma = O.preconditioner_sigma()
+    for k in (1, 3):
+        u = np.random.default_rng(40 + k).standard_normal((nV, k))
+        L = O.fractional_apply(V, F, u, sigma)
+        Ls = O.fractional_at_vertices(V, F, u, verts, sigma)
+        assert np.abs(Ls - L[verts]).max() <= 1e-13 * np.abs(L).max()
+
+
+@pytest.mark.parametrize("p", [6.0, 3.0])
+def test_implicit_obstacle_is_a_barrier(p):
+    """A repelling implicit obstacle (Sec. 7.3.3) is a barrier: a barycenter on the far side
+    of the plane gives +infinity whatever the parity of p (d^-p alone is finite and positive
+    for an even p and negative for an odd one), and the Armijo search treats a non-finite
+    objective as a failed test, so a first trial step that jumps across the plane is halved
+    until every barycenter stays on the near side."""
+    m = mg.workload("small_sphere")
+    X = O.faces(m.V, m.F)[0]
+    zmin = X[:, 2].min()
+    across = [dict(kind=0, q=[0.0, 0.0, 1.0], c=zmin + 1e-3, p=p, w=1.0, attract=False)]
+    assert O.implicit_potential(m.V, m.F, across, False)[0] == np.inf
+    plane = [dict(kind=0, q=[0.0, 0.0, 1.0], c=zmin - 0.02, p=p, w=1e-14, attract=False)]
+    r = O.precond_step(m.V, m.F, constrain_area=False, constrain_volume=False, implicit=plane)
+    tau0 = 0.5 * O._mean_edge_length(m.V, m.F) / np.linalg.norm(r.direction, axis=1).max()
+    d_tau0 = O.faces(m.V + tau0 * r.direction, m.F)[0][:, 2].min() - (zmin - 0.02)
+    assert d_tau0 < 0.0                       # the first trial crosses the plane
+    assert r.backtracks >= 1 and r.tau < tau0
+    d_new = O.faces(r.V, m.F)[0][:, 2].min() - (zmin - 0.02)
+    assert d_new > 0.0
+    assert np.isfinite(O.implicit_potential(r.V, m.F, plane, False)[0])
