@@ -24,6 +24,7 @@ CFLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result", "-Wno-unknown-pragmas",
+    "-I", os.path.join(os.path.dirname(HERE), "include"),
 ]
 
 

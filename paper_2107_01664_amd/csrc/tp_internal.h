@@ -6,7 +6,7 @@
 
 #include <string>
 
-#include "../../include/tpsurf.h"
+#include "tpsurf.h"
 
 namespace tp {
 

@@ -14,7 +14,8 @@
 // FP32 over kTileJ terms, then added into FP64 accumulators.  With HILO the barycenter
 // difference is formed as (Xhi_S - Xhi_T) + (Xlo_S - Xlo_T) from an FP32 hi/lo split of
 // the FP64 barycenter, which keeps d accurate for near pairs (the kernel raises q = N.d
-// to the 6th power, and q is small for near pairs on a smooth surface).
+// to the 6th power, and q is small for near pairs on a smooth surface); tiles far from
+// the i-range (tile_is_far) use the high parts alone.
 #include "tp_internal.h"
 
 #include <hipcub/hipcub.hpp>
@@ -170,6 +171,28 @@ __device__ __forceinline__ bool tile_may_be_near(const float4& ilo, const float4
     return gx * gx + gy * gy + gz * gz <= 1.01f * rho2;
 }
 
+// Far tiles drop the low parts of the barycenters.  Without them the difference of two
+// barycenters carries an absolute error of at most 2^-24 (|X_S| + |X_T|) per coordinate
+// (the rounding of X to FP32) instead of 2^-24 |X_S - X_T| with them.  When every pair of
+// the i-range box and the j-tile box is at least kFarRatio x the largest coordinate
+// magnitude of the two boxes apart, that error is at most 2 / kFarRatio = 8 times the
+// rounding of the hi/lo difference, on pairs whose terms fall off as |d|^-7 or faster.
+constexpr float kFarRatio = 0.25f;
+
+__device__ __forceinline__ bool tile_is_far(const float4& ilo, const float4& ihi, const float4* tbox, int jt)
+{
+    const float4 a = tbox[2 * jt], b = tbox[2 * jt + 1];
+    const float gx = fmaxf(fmaxf(a.x - ihi.x, ilo.x - b.x), 0.f);
+    const float gy = fmaxf(fmaxf(a.y - ihi.y, ilo.y - b.y), 0.f);
+    const float gz = fmaxf(fmaxf(a.z - ihi.z, ilo.z - b.z), 0.f);
+    const float m = fmaxf(fmaxf(fmaxf(fabsf(a.x), fabsf(b.x)), fmaxf(fabsf(a.y), fabsf(b.y))),
+                          fmaxf(fmaxf(fabsf(a.z), fabsf(b.z)),
+                                fmaxf(fmaxf(fmaxf(fabsf(ilo.x), fabsf(ihi.x)), fmaxf(fabsf(ilo.y), fabsf(ihi.y))),
+                                      fmaxf(fabsf(ilo.z), fabsf(ihi.z)))));
+    const float g2 = gx * gx + gy * gy + gz * gz;
+    return g2 >= (kFarRatio * kFarRatio) * (m * m);   // false for empty boxes (m = inf)
+}
+
 // ============================================================== energy (FP32)
 
 // Squared FP32 distance of a pair, in one fixed sequence of operations (the FP64 near
@@ -246,7 +269,7 @@ __global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
         acc[r] = 0.0;
     }
     float4 ilo, ihi;
-    if (NEAR) irange_box(J.tbox, ibase, kBlock * NI, ilo, ihi);
+    if (NEAR || HILO) irange_box(J.tbox, ibase, kBlock * NI, ilo, ihi);
     for (int jt = jt0; jt < jt1; ++jt) {
         const int64_t j0 = (int64_t)jt * kTileJ;
         __syncthreads();
@@ -259,6 +282,8 @@ __global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
             energy_tile32<true, NI, HILO, NEAR>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
         else if (NEAR && tile_may_be_near(ilo, ihi, J.tbox, jt, J.rho2))
             energy_tile32<false, NI, HILO, NEAR>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
+        else if (HILO && tile_is_far(ilo, ihi, J.tbox, jt))
+            energy_tile32<false, NI, false, false>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
         else
             energy_tile32<false, NI, HILO, false>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
 #pragma unroll
@@ -374,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_grad32(PairBatch jb, double alpha, d
         for (int m = 0; m < kGradAcc; ++m) acc[r][m] = 0.0;
     }
     float4 ilo, ihi;
-    if (NEAR) irange_box(J.tbox, ibase, kBlock * NI, ilo, ihi);
+    if (NEAR || HILO) irange_box(J.tbox, ibase, kBlock * NI, ilo, ihi);
     for (int jt = jt0; jt < jt1; ++jt) {
         const int64_t j0 = (int64_t)jt * kTileJ;
         __syncthreads();
@@ -389,6 +414,8 @@ __global__ __launch_bounds__(kBlock) void k_grad32(PairBatch jb, double alpha, d
             grad_tile32<true, NI, HILO, NEAR>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
         else if (NEAR && tile_may_be_near(ilo, ihi, J.tbox, jt, J.rho2))
             grad_tile32<false, NI, HILO, NEAR>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
+        else if (HILO && tile_is_far(ilo, ihi, J.tbox, jt))
+            grad_tile32<false, NI, false, false>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
         else
             grad_tile32<false, NI, HILO, false>(s_x, s_l, s_n, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
 #pragma unroll
@@ -503,6 +530,8 @@ __global__ __launch_bounds__(kBlock) void k_frac32(PairBatch jb, float expo)
             acc[r][cc] = 0.0;
         }
     }
+    float4 ilo, ihi;
+    if (HILO) irange_box(J.tbox, ibase, kBlock * NI, ilo, ihi);
     for (int jt = jt0; jt < jt1; ++jt) {
         const int64_t j0 = (int64_t)jt * kTileJ;
         __syncthreads();
@@ -520,6 +549,8 @@ __global__ __launch_bounds__(kBlock) void k_frac32(PairBatch jb, float expo)
             for (int cc = 0; cc < KC; ++cc) c[r][cc] = 0.f;
         if (tile_hits_diag(j0, ibase, kBlock * NI))
             frac_tile32<true, NI, KC, HILO>(s_x, s_l, s_u, j0, Sh, Sl, Su, Si, expo, c);
+        else if (HILO && tile_is_far(ilo, ihi, J.tbox, jt))
+            frac_tile32<false, NI, KC, false>(s_x, s_l, s_u, j0, Sh, Sl, Su, Si, expo, c);
         else
             frac_tile32<false, NI, KC, HILO>(s_x, s_l, s_u, j0, Sh, Sl, Su, Si, expo, c);
 #pragma unroll
