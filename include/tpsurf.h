@@ -112,6 +112,19 @@ TP_API tp_status tp_gradient(const double* V, int64_t nV, const int32_t* F, int6
 TP_API tp_status tp_energy_faces(const double* X, const double* N, const double* a, int64_t nF,
                           const tp_params* params, double* E_out, void* stream);
 
+/* tp_energy_faces without any allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same arguments, kernels and result as tp_energy_faces (partial sums may be split
+ * differently, so the last bits can differ).  All device scratch lives in one static
+ * device array of 32 MiB that each GPU the library runs on holds until the process ends;
+ * nF is limited to 2 <= nF <= 65536 (TP_E_INVALID_ARGUMENT above that, before any device
+ * work).  theta > 0 and TP_PREC_FP32_NEAR64 are rejected as in tp_energy_faces.  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (other streams or
+ * threads) race and must be serialised by the caller.  The call returns after the result
+ * has been copied to E_out (a stream synchronisation). */
+TP_API tp_status tp_energy_faces_noalloc(const double* X, const double* N, const double* a, int64_t nF,
+                                  const tp_params* params, double* E_out, void* stream);
+
 /* Lu = L^sigma u for k columns (eq. DiscreteLaplacianQuartic, factored as
  * 2 U^T [diag(diag(a)^-1 H a) - H] U of Sec. 5.1.1, H_ST = (1 - delta_ST)|X_S - X_T|^-(2 sigma + 2)).
  * u, Lu_out: device, nV x k row-major double, 1 <= k <= 64. */

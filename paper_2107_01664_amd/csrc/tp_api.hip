@@ -2438,6 +2438,52 @@ tp_status bind(tp_problem* P)
 
 }  // namespace
 
+// ------------------------------------------------------------------ allocation-free energy
+//
+// tp_energy_faces_noalloc keeps all of its device scratch (face data, partial sums,
+// reduction scratch, flags and the result) in one file-scope device array, so it never
+// allocates.  Each GPU the library runs on holds its own copy until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns on that device.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+constexpr int64_t kNoAllocMaxFaces = 65536;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+struct ScratchAddresses {
+    std::mutex mu;
+    void* p[64] = {};
+};
+ScratchAddresses g_scratch;
+
+// The device address of `scratch` on the current device (looked up once per device).
+tp_status scratch_address(unsigned char** out)
+{
+    int dev = 0;
+    TP_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(TP_E_DEVICE, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch.mu);
+    if (!g_scratch.p[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(TP_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        }
+        g_scratch.p[dev] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch.p[dev]);
+    return TP_OK;
+}
+
+__global__ void k_zero_ints(int* __restrict__ p, int n)
+{
+    const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
 // ======================================================================== C-ABI
 
 extern "C" {
@@ -2796,6 +2842,92 @@ tp_status tp_energy_faces(const double* X, const double* N, const double* a, int
     TP_HIP(launch_face_from_quantities(X, N, a, nF, P->fd, P->flags.p, P->stream));
     TP_TRY(check_flags(P));
     return run_energy(P, E_out);
+}
+
+tp_status tp_energy_faces_noalloc(const double* X, const double* N, const double* a, int64_t nF,
+                                  const tp_params* params, double* E_out, void* stream)
+{
+    set_error("");
+    if (!X || !N || !a || !E_out) return fail(TP_E_INVALID_ARGUMENT, "NULL argument");
+    if (nF < 2 || nF > kNoAllocMaxFaces)
+        return fail(TP_E_INVALID_ARGUMENT, "tp_energy_faces_noalloc needs 2 <= nF <= 65536");
+    tp_params prm;
+    double sigma = 0.0;
+    TP_TRY(validate_params(params, prm, sigma));
+    if (prm.theta > 0.0)
+        return fail(TP_E_INVALID_ARGUMENT, "Barnes-Hut (theta > 0) needs the mesh: use tp_energy or a problem");
+    if (prm.precision == TP_PREC_FP32_NEAR64)
+        return fail(TP_E_INVALID_ARGUMENT, "TP_PREC_FP32_NEAR64 needs the mesh: use tp_energy or a problem");
+    hipStream_t s = (hipStream_t)stream;
+    unsigned char* base = nullptr;
+    TP_TRY(scratch_address(&base));
+
+    // layout of the scratch: header (flags, result), reduction scratch, tile boxes, face
+    // data, reduced per-face sums, then as many j-splits of partial sums as fit
+    const int64_t cap = face_capacity(nF, 4);
+    PairPlan pl = plan_for(kKindEnergy, prm.precision, 1, nF, cap);
+    size_t off = 0;
+    auto take = [&off](size_t bytes) {
+        const size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const size_t o_hdr = take(64);
+    const size_t o_red = take(sizeof(double) * reduce_scratch_doubles(16));
+    const size_t o_box = take(sizeof(float4) * 2 * (size_t)(cap / kTileJ));
+    const size_t o_fx = take(sizeof(float4) * (size_t)cap);
+    const size_t o_fl = take(sizeof(float4) * (size_t)cap);
+    const size_t o_fn = take(sizeof(float4) * (size_t)cap);
+    const size_t o_dx = take(sizeof(double4) * (size_t)cap);
+    const size_t o_dn = take(sizeof(double4) * (size_t)cap);
+    const size_t o_gf = take(sizeof(double) * (size_t)pl.irows);
+    const size_t per_split = sizeof(double) * (size_t)pl.irows;
+    if (off + per_split > kNoAllocScratchBytes)
+        return fail(TP_E_INVALID_ARGUMENT, "nF too large for the scratch of tp_energy_faces_noalloc");
+    const int max_split = (int)std::min<size_t>((kNoAllocScratchBytes - off) / per_split, 1 << 20);
+    if (pl.n_split > max_split) {
+        pl.tiles_per_split = (pl.ntiles_j + max_split - 1) / max_split;
+        pl.n_split = (pl.ntiles_j + pl.tiles_per_split - 1) / pl.tiles_per_split;
+    }
+    const size_t o_part = take(per_split * (size_t)pl.n_split);
+    if (off > kNoAllocScratchBytes) return fail(TP_E_INVALID_ARGUMENT, "scratch layout exceeds its size");
+
+    int* flags = reinterpret_cast<int*>(base + o_hdr);
+    double* E_dev = reinterpret_cast<double*>(base + o_hdr + 16);
+    double* red = reinterpret_cast<double*>(base + o_red);
+    FaceData fd;
+    fd.nF = nF;
+    fd.cap = cap;
+    fd.tbox = reinterpret_cast<float4*>(base + o_box);
+    fd.fx = reinterpret_cast<float4*>(base + o_fx);
+    fd.fl = reinterpret_cast<float4*>(base + o_fl);
+    fd.fn = reinterpret_cast<float4*>(base + o_fn);
+    fd.dx = reinterpret_cast<double4*>(base + o_dx);
+    fd.dn = reinterpret_cast<double4*>(base + o_dn);
+    double* gface = reinterpret_cast<double*>(base + o_gf);
+    double* part = reinterpret_cast<double*>(base + o_part);
+
+    // flags start at zero (a fill kernel, so the sequence can be captured in a graph);
+    // every other region is written before it is read
+    hipLaunchKernelGGL(k_zero_ints, dim3(1), dim3(64), 0, s, flags, kNumFlags);
+    TP_HIP(hipGetLastError());
+    TP_HIP(launch_face_from_quantities(X, N, a, nF, fd, flags, s));
+    const PairJob J = make_pair_job(fd, pl, part);
+    TP_HIP(launch_pairs_energy(&J, 1, prm.precision, prm.alpha, prm.beta, s));
+    TP_HIP(launch_reduce_splits(part, pl.n_split, 1, pl.irows, nF, gface, pl.irows, s));
+    TP_HIP(launch_dot_cols(&fd.dx[0].w, 4, gface, 1, nF, 1, red, E_dev, s));
+    struct {
+        int flags[kNumFlags];
+        double E;
+    } h;
+    static_assert(sizeof(h) == 16 + sizeof(double), "header layout: flags at 0, the result at 16");
+    TP_HIP(hipMemcpyAsync(&h, base + o_hdr, sizeof(h), hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    if (h.flags[kFlagNonFinite]) return fail(TP_E_NONFINITE, "non-finite vertex coordinates or face quantities");
+    if (h.flags[kFlagDegenerate]) return fail(TP_E_DEGENERATE_FACE, "a face has zero area (its normal is undefined)");
+    *E_out = h.E;
+    if (!std::isfinite(h.E)) return fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
+    return TP_OK;
 }
 
 tp_status tp_problem_bh_stats(tp_problem* P, int64_t* far_terms, int64_t* near_terms)

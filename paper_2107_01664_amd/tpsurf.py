@@ -30,7 +30,8 @@ KIND_ENERGY, KIND_GRAD, KIND_FRAC, KIND_SOBOLEV = 0, 1, 2, 3
 
 # Every symbol the C-ABI exports (the header declares exactly these).
 EXPORTED = [
-    "tp_params_default", "tp_energy", "tp_gradient", "tp_energy_faces", "tp_fractional_apply",
+    "tp_params_default", "tp_energy", "tp_gradient", "tp_energy_faces", "tp_energy_faces_noalloc",
+    "tp_fractional_apply",
     "tp_precond_apply", "tp_problem_create", "tp_problem_destroy", "tp_problem_set_vertices",
     "tp_problem_get_vertices", "tp_problem_energy", "tp_problem_gradient",
     "tp_problem_fractional_apply", "tp_sobolev_apply", "tp_problem_sobolev_apply",
@@ -114,6 +115,7 @@ def lib() -> ctypes.CDLL:
         "tp_energy": [vp, i64, vp, i64, P(Params), P(d), vp],
         "tp_gradient": [vp, i64, vp, i64, P(Params), P(d), vp, vp],
         "tp_energy_faces": [vp, vp, vp, i64, P(Params), P(d), vp],
+        "tp_energy_faces_noalloc": [vp, vp, vp, i64, P(Params), P(d), vp],
         "tp_fractional_apply": [vp, i64, vp, i64, P(Params), vp, i32, vp, vp],
         "tp_precond_apply": [vp, i64, vp, i64, P(Params), vp, i32, vp, P(SolveReport), vp],
         "tp_problem_create": [vp, i64, vp, i64, P(Params), vp, P(vp)],
@@ -212,6 +214,17 @@ def tp_energy_faces(X, N, a, params: Optional[Params] = None) -> float:
     E = ctypes.c_double()
     _check(lib().tp_energy_faces(X.data_ptr(), N.data_ptr(), a.data_ptr(), a.shape[0],
                                  ctypes.byref(params or default_params()), ctypes.byref(E), _stream()))
+    return E.value
+
+
+def tp_energy_faces_noalloc(X, N, a, params: Optional[Params] = None) -> float:
+    """tp_energy_faces through the entry point that allocates nothing (nF <= 65536)."""
+    X = _dev(X, torch.float64, "X", 3)
+    N = _dev(N, torch.float64, "N", 3)
+    a = _dev(a, torch.float64, "a")
+    E = ctypes.c_double()
+    _check(lib().tp_energy_faces_noalloc(X.data_ptr(), N.data_ptr(), a.data_ptr(), a.shape[0],
+                                         ctypes.byref(params or default_params()), ctypes.byref(E), _stream()))
     return E.value
 
 
