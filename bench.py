@@ -114,6 +114,72 @@ def gmres_report(P, dE) -> dict:
     return out
 
 
+def accuracy_report(tp, V, F, u, E, dE, Lu) -> dict:
+    """Each result of the step's FP32 path against the FP64 path of the same library on the
+    same inputs (FP64 pair terms; the GPU tests hold that path to the FP64 oracle)."""
+    import numpy as np
+
+    with tp.Problem(V, F, tp.default_params(precision=2)) as P64:
+        E64, g64 = P64.gradient()
+        L64 = P64.fractional_apply(u)
+    g64, L64 = g64.cpu().numpy(), L64.cpu().numpy()
+    dE, Lu = dE.cpu().numpy(), Lu.cpu().numpy()
+    return {"reference": "fp64 pair terms on the GPU (held to the FP64 oracle by the GPU tests)",
+            "E_rel": abs(E - E64) / abs(E64),
+            "dE_rel": float(np.linalg.norm(dE - g64) / np.linalg.norm(g64)),
+            "Lu_rel": float(np.linalg.norm(Lu - L64) / np.linalg.norm(L64))}
+
+
+def descent_step_report(tp, V, F, steps: int = 4) -> dict:
+    """The full descent step (tp_precond_step: E + dE, A~^{-1} on the 9 columns of
+    [dE, J_A, J_V], Schur system, Armijo, corrective projection) on the bench mesh, with the
+    Poisson solves started from zero and warm-started from the previous step."""
+    import numpy as np
+
+    out = {}
+    for name, warm in (("cold", 0), ("warm_start", 1)):
+        with tp.Problem(V, F) as P:
+            reps = [P.step(tp.step_opts(warm_start=warm)) for _ in range(steps + 1)]
+        later = reps[1:]
+        out[name] = {"ms": float(np.mean([r.t_ms[6] for r in later])),
+                     "precond_ms": float(np.mean([r.t_ms[2] for r in later])),
+                     "cg_iters": [list(r.cg_iters) for r in later],
+                     "warm_started": [int(r.warm_started) for r in later]}
+    out["steps_timed"] = steps
+    out["note"] = "device ms per step (the step's own events), steps 2..%d of a fresh problem" % (steps + 1)
+    return out
+
+
+def cpu_info() -> dict:
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_cpus": os.cpu_count()}
+
+
+def cpu_one_core_rate(seconds: float = 3.0) -> float:
+    """Ordered E + dE pair terms per second of the oracle on one core (a child process with
+    OMP_NUM_THREADS=1, a band of rows of the bench mesh)."""
+    import subprocess
+    code = ("import sys, time; sys.path.insert(0, %r)\n"
+            "import oracle as O\n"
+            "from paper_2107_01664_amd import meshgen as mg\n"
+            "m = mg.workload('torus40k'); O.lib(); O.gradient_rows(m.V, m.F, 0, 4)\n"
+            "t = time.perf_counter(); O.gradient_rows(m.V, m.F, 0, 16); dt = time.perf_counter() - t\n"
+            "n = max(16, int(16 * %f / max(dt, 1e-6)))\n"
+            "t = time.perf_counter(); O.gradient_rows(m.V, m.F, 0, n); dt = time.perf_counter() - t\n"
+            "print(n * (m.nF - 1) / dt)\n") % (ROOT, seconds)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=300)
+    return float(r.stdout.strip().splitlines()[-1]) if r.returncode == 0 and r.stdout.strip() else float("nan")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -477,6 +543,10 @@ def main():
     cg_ms = [float(np.mean([r.t_ms[0] for r in reps])), float(np.mean([r.t_ms[2] for r in reps]))]
     sob = sobolev_report(tp, P, u)
     gm = gmres_report(P, dE)
+    P.gradient(out=dE)
+    P.fractional_apply(u, out=Lu)
+    acc = accuracy_report(tp, V, F, u, E, dE, Lu)
+    dstep = descent_step_report(tp, V, F)
 
     out = {
         "metric": "tri-pair interactions/s (E+dE, H-apply) vs FP32 roofline; served steps/s + p99",
@@ -535,6 +605,8 @@ def main():
             "pcg": pcg_report(mesh.nV, 3, cg_ms, [int(reps[-1].cg_iters[0]), int(reps[-1].cg_iters[1])]),
         },
         "energy": E,
+        "accuracy_vs_fp64": acc,
+        "descent_step": dstep,
     }
     P.close()
     if a.serve_requests > 0:
@@ -542,6 +614,11 @@ def main():
                                        a.serve_steps, a.serve_fmax)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, u_np, a.cpu_seconds)
+        out["cpu_baseline"].update(cpu_info())
+        one = cpu_one_core_rate()
+        out["cpu_baseline"]["one_core_pairs_per_s"] = one
+        out["cpu_baseline"]["one_core_note"] = ("ordered E + dE pair terms per second of the oracle on one "
+                                                "core (OMP_NUM_THREADS=1), a band of rows of the same mesh")
     print(json.dumps(out), flush=True)
 
 

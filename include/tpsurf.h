@@ -28,7 +28,9 @@
  *   - Errors are returned as tp_status; no exception crosses the ABI.  tp_last_error()
  *     gives a message for the calling thread.  On error the outputs are undefined, except
  *     for TP_E_NOT_CONVERGED, where outputs and reports are written.
- *   - Results are deterministic: no floating-point atomics, fixed reduction orders.
+ *   - Results are deterministic (fixed reduction orders, no floating-point atomics), with
+ *     one exception: the Barnes-Hut differential (theta > 0) adds its target-side terms
+ *     with floating-point atomics, so its last bits can differ from run to run.
  */
 #ifndef TPSURF_H
 #define TPSURF_H
@@ -298,6 +300,11 @@ typedef struct {
                                 component's mean, and the translation by minus the
                                 vertex-area-weighted mean of dE (of the total objective)
                                 over the component is added back to the direction; default 0 */
+    int    warm_start;       /* 1 (default): the two Poisson solves of the preconditioner
+                                start from the previous step's solutions of this problem
+                                (same columns, one-launch preconditioned CG; the tolerance
+                                stays relative to |b|); 0: from x = 0 (the paper's solve).
+                                The first step of a problem always starts from zero       */
 } tp_step_opts;
 
 TP_API tp_status tp_step_opts_default(tp_step_opts* o);
@@ -322,6 +329,8 @@ typedef struct {
                                 apply), [3] Schur system and direction, [4] line search,
                                 [5] corrective projection and new energy, [6] whole step;
                                 [7] number of problems whose launches this step shared    */
+    int    warm_started;     /* 1 if the Poisson solves started from the previous step's
+                                solutions                                                 */
 } tp_step_report;
 
 /* One projected, preconditioned descent step (the basic step of Sec. 3 with Sec. 5.3-5.4):
@@ -377,6 +386,22 @@ TP_API tp_status tp_problem_bh_stats(tp_problem* prob, int64_t* far_terms, int64
 
 /* Message describing the last error of the calling thread ("" if none). */
 TP_API const char* tp_last_error(void);
+
+/* Device memory of the library.  By default every device buffer (resident problem state,
+ * work arrays, temporaries of the stateless calls) comes from hipMalloc.  With an
+ * allocator registered, every device buffer allocated afterwards comes from
+ * alloc(bytes, stream, user) -- stream is the hipStream_t the buffer is first used on --
+ * and is returned with free_(ptr, bytes, stream, user); a NULL result of alloc is
+ * TP_E_OUT_OF_MEMORY.  This lets the caller's allocator (for example PyTorch's caching
+ * allocator) own all device memory.  Pinned host buffers for read-backs still use
+ * hipHostMalloc.  alloc = free_ = NULL restores hipMalloc.  The registration is
+ * process-global and may change only while no buffer of the registered allocator is
+ * alive (TP_E_INVALID_ARGUMENT otherwise): register before creating problems, and destroy
+ * them before unregistering.  Both functions must be callable from any thread that calls
+ * the library and must not call back into it. */
+typedef void* (*tp_alloc_fn)(size_t bytes, void* stream, void* user);
+typedef void (*tp_free_fn)(void* ptr, size_t bytes, void* stream, void* user);
+TP_API tp_status tp_set_allocator(tp_alloc_fn alloc, tp_free_fn free_, void* user);
 
 /* Kernel timing for roofline reports.  When enabled, every all-pairs kernel launch is
  * bracketed by HIP events recorded on the stream it runs on; the elapsed device time,

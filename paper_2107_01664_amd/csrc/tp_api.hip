@@ -99,20 +99,46 @@ struct PairTimer {
 };
 
 // ------------------------------------------------------------------ device buffers
+//
+// Device memory comes from the allocator registered with tp_set_allocator (for example
+// the caller's caching allocator) or, when none is registered, from hipMalloc.  Each
+// buffer keeps the free function that matches its allocation.
+
+struct AllocatorState {
+    std::mutex mu;
+    tp_alloc_fn alloc = nullptr;
+    tp_free_fn free_ = nullptr;
+    void* user = nullptr;
+    int64_t live = 0;     // buffers allocated through the registered allocator and not freed
+};
+static AllocatorState g_alloc;
 
 template <class T>
 struct DevBuf {
     T* p = nullptr;
     size_t n = 0;
+    tp_free_fn fr = nullptr;     // free function of the registered allocator (null: hipFree)
+    void* fr_user = nullptr;
+    hipStream_t fr_stream = nullptr;
     DevBuf() = default;
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     ~DevBuf() { release(); }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (fr) {
+                fr(p, n * sizeof(T), fr_stream, fr_user);
+                std::lock_guard<std::mutex> lk(g_alloc.mu);
+                --g_alloc.live;
+            } else {
+                (void)hipFree(p);
+            }
+        }
         p = nullptr;
         n = 0;
+        fr = nullptr;
+        fr_user = nullptr;
     }
     size_t bytes() const { return n * sizeof(T); }
     // Grow to at least cnt elements (contents are not preserved).
@@ -123,11 +149,35 @@ struct DevBuf {
             if (hipStreamSynchronize(s) != hipSuccess) return fail(TP_E_DEVICE, "stream sync failed");
             release();
         }
-        size_t want = std::max<size_t>(cnt, 1);
-        if (hipMalloc((void**)&p, want * sizeof(T)) != hipSuccess) {
+        const size_t want = std::max<size_t>(cnt, 1);
+        const size_t bytes = want * sizeof(T);
+        tp_alloc_fn a = nullptr;
+        tp_free_fn f = nullptr;
+        void* u = nullptr;
+        {
+            // the registered functions are called without the lock held: they may run
+            // arbitrary caller code (which may free other buffers of the library)
+            std::lock_guard<std::mutex> lk(g_alloc.mu);
+            a = g_alloc.alloc;
+            f = g_alloc.free_;
+            u = g_alloc.user;
+            if (a) ++g_alloc.live;
+        }
+        if (a) {
+            void* q = a(bytes, s, u);
+            if (!q) {
+                std::lock_guard<std::mutex> lk(g_alloc.mu);
+                --g_alloc.live;
+                return fail(TP_E_OUT_OF_MEMORY, "the registered allocator returned NULL for " + std::to_string(bytes) + " bytes");
+            }
+            p = static_cast<T*>(q);
+            fr = f;
+            fr_user = u;
+            fr_stream = s;
+        } else if (hipMalloc((void**)&p, bytes) != hipSuccess) {
             p = nullptr;
             (void)hipGetLastError();
-            return fail(TP_E_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(want * sizeof(T)) + " bytes failed");
+            return fail(TP_E_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
         }
         n = want;
         return TP_OK;
@@ -248,6 +298,9 @@ struct tp_problem {
     int64_t nnz = 0;
     int ncomp = 0;
     int last_iters = 0;              // iterations of the problem's last solve (launch grouping)
+    int warm_cols = 0;               // > 0: W2 and Y hold the solutions of the last step's two
+                                     // Poisson solves with this many columns (warm start)
+    bool warm_now = false;           // this step's solves start from them
 
     double area0 = 0, vol0 = 0, mean_edge = 0;
 
@@ -1119,7 +1172,7 @@ tp_status pcg_table_slot(tp_problem* O, int n, void** dev, void** host, int* slo
 // x[m] = C^+ b[m] for k columns (row stride k) of every problem; b[m] is overwritten with
 // its per-component mean-zero projection.  Iteration counts and final relative residuals
 // go to the pinned mirrors at offset which * kMaxCols (read them after a sync).
-tp_status enqueue_cg(const Batch& B, double* const* b, double* const* x, int k, int which)
+tp_status enqueue_cg(const Batch& B, double* const* b, double* const* x, int k, int which, bool warm = false)
 {
     if (B.empty()) return TP_OK;
     hipStream_t s = B[0]->stream;
@@ -1167,6 +1220,10 @@ tp_status enqueue_cg(const Batch& B, double* const* b, double* const* x, int k, 
                 it.ps = &P->pcg;
                 it.b = P->pcg_bp.p;
                 it.x = P->pcg_xp.p;
+                // warm start: x[m] still holds this solve's solution of the last step
+                it.warm = warm && P->warm_now ? 1 : 0;
+                if (it.warm)
+                    TP_HIP(launch_permute_rows(P->nV, kc, P->pcg.perm, k, c0, x[pc[q]], P->pcg_xp.p, true, s));
                 it.w.Vb = P->pcg_Vb.p; it.w.rho = P->pcg_rho.p; it.w.red = P->pcg_red.p;
                 it.w.bar = P->cg_bar.p; it.w.flags = P->flags.p;
                 it.w.iters = P->cg_iters.p + c0;
@@ -1249,7 +1306,7 @@ struct EventTimer {
 // Y[m] = A~^{-1} R[m] = C^+ L^sigma C^+ R[m] columnwise (k columns, row stride k); R is
 // not modified.  Uses W1, W2 of every problem.
 tp_status enqueue_precond(const Batch& B, const double* const* R, int k, double* const* Y,
-                          EventTimer* tm, int mark0)
+                          EventTimer* tm, int mark0, bool warm = false)
 {
     if (B.empty()) return TP_OK;
     hipStream_t s = B[0]->stream;
@@ -1266,11 +1323,14 @@ tp_status enqueue_precond(const Batch& B, const double* const* R, int k, double*
         w2[m] = P->W2.p;
         w2c[m] = P->W2.p;
     }
-    TP_TRY(enqueue_cg(B, w1.data(), w2.data(), k, 0));      // W2 = C^+ P R
+    TP_TRY(enqueue_cg(B, w1.data(), w2.data(), k, 0, warm));      // W2 = C^+ P R
     if (tm) tm->mark(mark0);
     TP_TRY(enqueue_fractional(B, w2c.data(), k, k, w1.data(), k));   // W1 = L W2
     if (tm) tm->mark(mark0 + 1);
-    TP_TRY(enqueue_cg(B, w1.data(), Y, k, 1));               // Y = C^+ P W1
+    TP_TRY(enqueue_cg(B, w1.data(), Y, k, 1, warm));               // Y = C^+ P W1
+    // W2 now holds this call's first solution: a later step may start from it only when
+    // it came from a step (which then sets warm_cols again)
+    for (tp_problem* P : B) P->warm_cols = 0;
     if (tm) tm->mark(mark0 + 2);
     return TP_OK;
 }
@@ -2019,11 +2079,18 @@ tp_status step_group(std::vector<StepState*>& G)
     } else {
         std::vector<const double*> Rp;
         std::vector<double*> Yp;
-        for (tp_problem* P : B) {
+        for (StepState* S : G) {
+            tp_problem* P = S->P;
             Rp.push_back(P->R.p);
             Yp.push_back(P->Y.p);
+            P->warm_now = S->o.warm_start && P->warm_cols == ncol && !S->penalized();
+            S->R.warm_started = P->warm_now ? 1 : 0;
         }
-        TP_TRY(enqueue_precond(B, Rp.data(), ncol, Yp.data(), &tm, 2));
+        TP_TRY(enqueue_precond(B, Rp.data(), ncol, Yp.data(), &tm, 2, true));
+        for (tp_problem* P : B) {
+            P->warm_now = false;
+            P->warm_cols = ncol;
+        }
     }
     // 4. Schur system S = J Y and J y_g (device dot products of 3 columns each)
     for (StepState* S : G) {
@@ -2521,6 +2588,7 @@ tp_status tp_step_opts_default(tp_step_opts* o)
     o->area_penalty = 0.0;
     o->volume_penalty = 0.0;
     o->barycenter_motion = 0;
+    o->warm_start = 1;
     return TP_OK;
 }
 
@@ -2969,6 +3037,21 @@ tp_status tp_profile_enable(int on)
 {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.on = on != 0;
+    return TP_OK;
+}
+
+tp_status tp_set_allocator(tp_alloc_fn alloc, tp_free_fn free_, void* user)
+{
+    set_error("");
+    if ((alloc == nullptr) != (free_ == nullptr))
+        return fail(TP_E_INVALID_ARGUMENT, "give both an allocation and a free function, or neither");
+    std::lock_guard<std::mutex> lk(g_alloc.mu);
+    if (g_alloc.live != 0)
+        return fail(TP_E_INVALID_ARGUMENT, std::to_string(g_alloc.live) +
+                                               " buffers from the registered allocator are still alive (destroy the problems first)");
+    g_alloc.alloc = alloc;
+    g_alloc.free_ = free_;
+    g_alloc.user = user;
     return TP_OK;
 }
 

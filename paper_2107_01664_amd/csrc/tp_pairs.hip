@@ -71,16 +71,23 @@ struct PowP6 {
     }
 };
 
-// General exponents through log2 / exp2.
+// General exponents through log2 / exp2, written on u = q / r2 (the same quantity the
+// p = 6 policy raises to integer powers):
+//   K = |u|^alpha r2^gamma,   Kqr = sgn(q) |u|^(alpha-1) r2^gamma,   gamma = alpha - beta/2.
+// The FP32 exponent (alpha-1) log2|u| + gamma log2 r2 then stays small: |u| is of the order
+// of the curvature and gamma is zero for beta = 2 alpha.  Written on q and r2 separately,
+// the two logarithms are each tens of units and cancel, and the FP32 rounding of those
+// terms becomes a relative error of K several times larger.
 struct PowGen {
     float am1;      // alpha - 1
-    float hb;       // beta / 2
+    float gam;      // alpha - beta / 2
     double am1d, hbd;
     __device__ __forceinline__ float K(float q, float r2, float inv) const
     {
-        (void)inv;
-        float lq = log2_fast(fabsf(q));
-        return exp2_fast((am1 + 1.0f) * lq - hb * log2_fast(r2));
+        if (r2 == INFINITY) return 0.0f;   // a pair left out of the FP32 sums
+        const float lu = log2_fast(fabsf(q * inv));
+        const float e = (am1 + 1.0f) * lu + (gam != 0.0f ? gam * log2_fast(r2) : 0.0f);
+        return exp2_fast(e);
     }
     __device__ __forceinline__ void KG(float q, float r2, float inv, float& K, float& Kqr) const
     {
@@ -89,9 +96,10 @@ struct PowGen {
             Kqr = 0.0f;
             return;
         }
-        float e = am1 * log2_fast(fabsf(q)) + (1.0f - hb) * log2_fast(r2);
+        const float u = q * inv;
+        const float e = am1 * log2_fast(fabsf(u)) + (gam != 0.0f ? gam * log2_fast(r2) : 0.0f);
         Kqr = copysignf(exp2_fast(e), q);
-        K = Kqr * q * inv;
+        K = Kqr * u;
     }
     __device__ __forceinline__ double K(double q, double r2, double inv) const
     {
@@ -1029,7 +1037,7 @@ PowGen make_gen(double alpha, double beta)
 {
     PowGen g;
     g.am1 = (float)(alpha - 1.0);
-    g.hb = (float)(beta * 0.5);
+    g.gam = (float)(alpha - 0.5 * beta);
     g.am1d = alpha - 1.0;
     g.hbd = beta * 0.5;
     return g;

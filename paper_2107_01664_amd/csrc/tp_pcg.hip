@@ -547,6 +547,7 @@ struct PcgArgs {
     int k;
     int block0;               // first workgroup of this problem in its launch
     int stage;                // the block shares fit the LDS staging area after PcgShared
+    int warm;                 // 1: x holds an initial guess (the previous solution)
 };
 
 constexpr int kCrowMax = 7680;      // cached coarse-inverse entries (FP32: 30 KB)
@@ -1040,14 +1041,29 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
     double my_bb = 0.0, my_rr = 0.0, my_gam = 0.0, my_alpha = 0.0;
     bool my_done = false;
     int my_its = 0;
+    double x0[KG];
 #pragma unroll
     for (int c = 0; c < KG; ++c) {
         r[c] = (act && c < k) ? A.b[i * k + c] : 0.0;
+        x0[c] = (A.warm && act && c < k) ? A.x[i * k + c] : 0.0;   // read before x is stored
         x[c] = 0.0;
     }
     int total_it = 0;
     constexpr int kMaxRestarts = 6;
     bool have_bb = false;
+    if (A.warm) {
+        // warm start: |b|^2 (the residual of x = 0) fixes the tolerance, then the solve
+        // starts from the residual of the previous solution
+        if (!true_residual()) return;
+        if (t < KG) {
+            my_bb = S.sums[t];
+            my_done = (t >= k) || !(my_bb > 0.0);
+        }
+        have_bb = true;
+#pragma unroll
+        for (int c = 0; c < KG; ++c) x[c] = x0[c];
+        if (!true_residual()) return;
+    }
     for (int cycle = 0; cycle <= kMaxRestarts; ++cycle) {
         // ---- a cycle starts from the current (true) residual r
 #pragma unroll
@@ -1244,6 +1260,7 @@ hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, v
         a.b = it.b; a.x = it.x; a.Vb = it.w.Vb; a.rho = it.w.rho; a.red = it.w.red; a.bar = it.w.bar;
         a.iters = it.w.iters; a.relres = it.w.relres; a.flags = it.w.flags;
         a.rtol = it.rtol; a.maxiter = it.maxiter; a.k = k; a.block0 = 0; a.stage = stage ? 1 : 0;
+        a.warm = it.warm ? 1 : 0;
         if ((int64_t)ps.nb > cap) return hipErrorCooperativeLaunchTooLarge;
     }
     // launches of consecutive problems whose workgroups are resident together

@@ -88,6 +88,7 @@ struct PcgItem {
     PcgWork w;
     double rtol = 1e-10;
     int maxiter = 1;
+    int warm = 0;             // 1: x holds the initial guess (tolerance still relative to |b|)
 };
 // Device table entries for n systems (tab_dev) and their pinned host staging (tab_host):
 // the host staging must not be rewritten before the copy enqueued here has run.

@@ -61,6 +61,19 @@ class Result:
         return out
 
 
+def count_components(F: np.ndarray, nV: int) -> int:
+    """Connected components of the mesh's vertex graph (edges of the faces); vertices used
+    by no face count as components of their own."""
+    import scipy.sparse as sp
+    from scipy.sparse.csgraph import connected_components
+
+    F = np.asarray(F)
+    r = np.concatenate([F[:, 0], F[:, 1]])
+    c = np.concatenate([F[:, 1], F[:, 2]])
+    G = sp.coo_matrix((np.ones(r.size, dtype=np.int8), (r, c)), shape=(nV, nV))
+    return int(connected_components(G, directed=False)[0])
+
+
 class GpuExecutor:
     """Executor over libtpsurf: one resident tp_problem per admitted request."""
 
@@ -77,8 +90,8 @@ class GpuExecutor:
     def estimate(self, req: Request) -> int:
         deg = np.bincount(req.F.reshape(-1), minlength=req.V.shape[0]).max()
         ncon = int(bool(self.opts.constrain_area)) + int(bool(self.opts.constrain_volume))
-        return self.tp.estimate_device_bytes(req.V.shape[0], req.F.shape[0], int(deg), 1,
-                                             self.params, ncon)
+        return self.tp.estimate_device_bytes(req.V.shape[0], req.F.shape[0], int(deg),
+                                             count_components(req.F, req.V.shape[0]), self.params, ncon)
 
     def create(self, req: Request):
         V = self.torch.from_numpy(np.ascontiguousarray(req.V, dtype=np.float64)).to(self.device)

@@ -40,7 +40,7 @@ EXPORTED = [
     "tp_problem_precond_apply", "tp_step_opts_default",
     "tp_precond_step", "tp_last_error", "tp_profile_enable", "tp_profile_reset", "tp_profile_get",
     "tp_problem_poisson_solve", "tp_batch_step", "tp_problem_device_bytes",
-    "tp_estimate_device_bytes", "tp_problem_bh_stats",
+    "tp_estimate_device_bytes", "tp_problem_bh_stats", "tp_set_allocator",
 ]
 
 
@@ -73,7 +73,7 @@ class StepOpts(ctypes.Structure):
                 ("area_target", ctypes.c_double), ("volume_target", ctypes.c_double),
                 ("solver", ctypes.c_int), ("solver_rtol", ctypes.c_double), ("solver_maxiter", ctypes.c_int),
                 ("area_penalty", ctypes.c_double), ("volume_penalty", ctypes.c_double),
-                ("barycenter_motion", ctypes.c_int)]
+                ("barycenter_motion", ctypes.c_int), ("warm_start", ctypes.c_int)]
 
 
 class StepReport(ctypes.Structure):
@@ -82,7 +82,7 @@ class StepReport(ctypes.Structure):
                 ("n_constraints", ctypes.c_int), ("cg_iters", ctypes.c_int * 2),
                 ("cg_relres", ctypes.c_double * 2), ("phi_before", ctypes.c_double * 2),
                 ("phi_trial", ctypes.c_double * 2), ("phi_after", ctypes.c_double * 2),
-                ("t_ms", ctypes.c_double * 8)]
+                ("t_ms", ctypes.c_double * 8), ("warm_started", ctypes.c_int)]
 
     def as_dict(self) -> dict:
         out = {}
@@ -142,6 +142,7 @@ def lib() -> ctypes.CDLL:
         "tp_profile_enable": [i32],
         "tp_profile_reset": [],
         "tp_profile_get": [i32, P(KernelStats)],
+        "tp_set_allocator": [ctypes.c_void_p, ctypes.c_void_p, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -153,6 +154,38 @@ def lib() -> ctypes.CDLL:
     L.tp_last_error.restype = ctypes.c_char_p
     _lib = L
     return L
+
+
+# tp_set_allocator callbacks: alloc(bytes, stream, user) -> pointer, free(ptr, bytes, stream, user)
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_torch_allocator = None     # the registered callbacks (kept alive while registered)
+allocator_calls = {"alloc": 0, "free": 0}
+
+
+def use_torch_allocator(on: bool = True) -> None:
+    """Route every device buffer of the library through PyTorch's caching allocator
+    (tp_set_allocator), or back to hipMalloc.  Switch only while no problem exists."""
+    global _torch_allocator
+    if not on:
+        _check(lib().tp_set_allocator(None, None, None))
+        _torch_allocator = None
+        return
+
+    def _alloc(nbytes, stream, user):
+        try:
+            allocator_calls["alloc"] += 1
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), int(stream or 0))
+        except Exception:       # reported to the library as NULL -> TP_E_OUT_OF_MEMORY
+            return None
+
+    def _free(ptr, nbytes, stream, user):
+        allocator_calls["free"] += 1
+        torch.cuda.caching_allocator_delete(ptr)
+
+    cbs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(lib().tp_set_allocator(ctypes.cast(cbs[0], ctypes.c_void_p), ctypes.cast(cbs[1], ctypes.c_void_p), None))
+    _torch_allocator = cbs
 
 
 def _check(status: int, allow=()):

@@ -157,3 +157,23 @@ def test_served_mix_equals_serial(tp):
     s = serve.summary(res)
     print("[serve] mix", s, flush=True)
     assert s["steps"] == 12
+
+
+def test_served_step_matches_oracle(tp):
+    """One served step per request of a small mix (continuous batching, two requests share
+    launches) against the oracle's step on the same mesh (Sec. 3 with Sec. 5.2-5.3, the
+    Armijo constants of the line search): same tau and backtracks, new vertices within
+    1e-4 of the oracle's displacement."""
+    import oracle as O
+    from paper_2107_01664_amd import serve
+    meshes = mix()[:3]
+    reqs = [serve.Request(q, 0.0, m.V, m.F.astype(np.int32), steps=1) for q, m in enumerate(meshes)]
+    res = serve.run(reqs, serve.GpuExecutor(), budget_bytes=8 << 30, max_active=3, keep_vertices=True)
+    assert max(max(r.batch_sizes) for r in res) >= 2
+    for r, m in zip(res, meshes):
+        print(f"[serve] request {r.rid} nF={m.nF}: oracle step", flush=True)
+        ref = O.precond_step(m.V, m.F)
+        disp = np.linalg.norm((r.vertices - m.V) - (ref.V - m.V)) / np.linalg.norm(ref.V - m.V)
+        print(f"  displacement error {disp:.2e}", flush=True)
+        assert r.status == 0
+        assert disp <= 1e-4, disp
