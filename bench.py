@@ -189,10 +189,14 @@ def parse():
                     help="0 fp32 hi/lo, 1 fp32, 2 fp64, 3 fp32 hi/lo + fp64 near field (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--serve-requests", type=int, default=48,
+    ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving comparison (0 skips it)")
-    ap.add_argument("--serve-fmax", type=float, default=20000.0)
-    ap.add_argument("--serve-steps", type=int, default=4)
+    ap.add_argument("--serve-fmax", type=float, default=200000.0)
+    ap.add_argument("--serve-steps", type=int, default=10)
+    ap.add_argument("--serve-capacity-requests", type=int, default=96,
+                    help="requests of the saturated serial pass that measures the serial capacity")
+    ap.add_argument("--serve-saturated", action="store_true",
+                    help="also serve the whole mix batched with every request present at t = 0")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving comparison and print its JSON line")
     ap.add_argument("--sweep", action="store_true",
@@ -362,6 +366,29 @@ def sweep():
             print(f"[sweep] {wname} {name}: {ms:.1f} ms, E {r['E_rel_err']:.2e}, dE {r['dE_rel_err']:.2e}",
                   file=sys.stderr, flush=True)
         report[wname] = {"faces": m.nF, "pairs": float(m.nF) * (m.nF - 1), "variants": rows}
+        # the fractional operator L^sigma u (3 random columns): direct sums, Barnes-Hut on the
+        # kernel matrix and the block cluster tree's hierarchical product, against the FP64
+        # direct sums; times of one synchronous call (best of 3)
+        u = torch.from_numpy(mg.random_columns(m.nV, 3, 1)).cuda()
+        frows, fref = {}, None
+        fvariants = [("fp64 direct", dict(precision=2)), ("fp32 hi/lo direct", dict(precision=3)),
+                     ("barnes-hut theta=0.5 fp32", dict(precision=0, theta=0.5)),
+                     ("block cluster tree chi=0.5 fp32", dict(precision=0, chi=0.5)),
+                     ("block cluster tree chi=0.25 fp32", dict(precision=0, chi=0.25))]
+        for name, kw in fvariants:
+            with tp.Problem(V, F, tp.default_params(**kw)) as P:
+                L, ms = _timed(lambda: P.fractional_apply(u))
+                L = L.cpu().numpy()
+                blocks = P.bct_stats() if kw.get("chi") else None
+            if fref is None:
+                fref = L
+                frows[name] = {"ms": ms}
+            else:
+                frows[name] = {"ms": ms, "Lu_rel_err": rel(L, fref)}
+                if blocks:
+                    frows[name]["blocks_admissible_inadmissible"] = list(blocks)
+            print(f"[sweep] {wname} L^sigma u {name}: {ms:.1f} ms", file=sys.stderr, flush=True)
+        report[wname]["fractional_apply"] = frows
     return report
 
 
@@ -387,12 +414,13 @@ def serving_meshes(n_req: int, fmax: float, steps: int, seed: int = 0, workers: 
 
 def serving_bench(specs, built, steps: int, fmax: float, seed: int = 0, load: float = 0.8,
                   max_active: int = 16, small_faces: int = 32768, max_large: int = 2,
-                  verbose: bool = False):
+                  verbose: bool = False, capacity_requests: int = 0, saturated: bool = True):
     """Continuous batching against the serial one-mesh-at-a-time path on the same requests:
     noisy icospheres / tori with F log-uniform in [2,000, fmax], `steps` descent steps
-    each.  The serial path first runs with every request present at t = 0, which gives its
-    capacity (and the batched path is run the same way); both paths then serve Poisson
-    arrivals at `load` x that capacity."""
+    each.  The serial path first runs with every request present at t = 0 -- the whole mix,
+    or its first `capacity_requests` requests -- which gives its capacity (requests/s); with
+    `saturated` the batched path is run the same way on the whole mix.  Both paths then
+    serve the whole mix with Poisson arrivals at `load` x that capacity."""
     import numpy as np
     from paper_2107_01664_amd import meshgen as mg
     from paper_2107_01664_amd import serve
@@ -412,11 +440,12 @@ def serving_bench(specs, built, steps: int, fmax: float, seed: int = 0, load: fl
     ex = serve.GpuExecutor()
     serve.run_serial(requests(np.zeros(1))[:1], ex)                  # warm-up
     zero = np.zeros(n_req)
-    sat_ser = serve.run_serial(requests(zero), ex, on_done=progress("saturated serial"))
+    n_cap = n_req if capacity_requests <= 0 else min(n_req, capacity_requests)
+    sat_ser = serve.run_serial(requests(zero)[:n_cap], ex, on_done=progress("saturated serial"))
     lanes = dict(small_faces=small_faces, max_large=max_large)
-    sat_bat = serve.run(requests(zero), ex, budget_bytes=200 << 30, max_active=max_active,
-                        on_done=progress("saturated batched"), **lanes)
-    cap = n_req / max(serve.summary(sat_ser)["makespan_s"], 1e-9)      # requests/s
+    sat_bat = (serve.run(requests(zero), ex, budget_bytes=200 << 30, max_active=max_active,
+                         on_done=progress("saturated batched"), **lanes) if saturated else None)
+    cap = n_cap / max(serve.summary(sat_ser)["makespan_s"], 1e-9)      # requests/s
     rate = load * cap
     arr = mg.poisson_arrivals(n_req, rate, seed + 1)
     bat = serve.run(requests(arr), ex, budget_bytes=200 << 30, max_active=max_active,
@@ -424,19 +453,28 @@ def serving_bench(specs, built, steps: int, fmax: float, seed: int = 0, load: fl
     ser = serve.run_serial(requests(arr), ex, keep_vertices=True, on_done=progress("poisson serial"))
     same = all(np.array_equal(a.vertices, b.vertices) for a, b in zip(bat, ser))
     nf = np.array([sp["nF"] for sp in specs], dtype=float)
-    return {
+    sb, ss = serve.summary(bat), serve.summary(ser)
+    out = {
         "workload": (f"{n_req} requests, noisy icosphere/torus, F log-uniform in [2000, {int(fmax)}] "
                      f"(mean {nf.mean():.0f}), {steps} preconditioned steps each (FP32 pair terms, FP64 CG, "
                      f"area + volume constraints, Armijo), Poisson arrivals at {load} x serial capacity "
                      f"({rate:.2f} requests/s); batched path: meshes of up to {small_faces} faces share "
-                     f"steps ({max_active} at most), larger ones ({max_large} admitted at most) step one at "
-                     f"a time between the shared steps; 'saturated': every request present at t = 0"),
+                     f"steps ({max_active} at most), larger ones ({max_large} admitted at most) step "
+                     f"oldest first, one at a time between the shared steps"),
         "serial_capacity_req_per_s": cap,
-        "saturated": {"batched": serve.summary(sat_bat), "serial": serve.summary(sat_ser)},
-        "batched": serve.summary(bat),
-        "serial": serve.summary(ser),
+        "serial_capacity_sample": (f"saturated serial pass over requests 0..{n_cap - 1} "
+                                   f"({serve.summary(sat_ser)['makespan_s']:.1f} s)"),
+        "batched": sb,
+        "serial": ss,
+        "steps_per_s": {"batched": sb["steps_per_s"], "serial": ss["steps_per_s"]},
+        "request_latency_p99_ms": {"batched": sb["request_latency_ms"]["p99"],
+                                   "serial": ss["request_latency_ms"]["p99"]},
         "all_requests_identical_to_serial": bool(same),
     }
+    if sat_bat is not None:
+        out["saturated"] = {"batched": serve.summary(sat_bat),
+                            "serial": serve.summary(sat_ser), "note": "serial: the capacity sample"}
+    return out
 
 
 def main():
@@ -447,7 +485,8 @@ def main():
         sys.exit(2)
 
     serve_mesh = None
-    if a.serve_only:        # build the request meshes in worker processes before any GPU use
+    if a.serve_requests > 0 and not (a.sweep or a.pairs_only or a.copy_probe or a.large_solve):
+        # build the request meshes in worker processes before any GPU use
         serve_mesh = serving_meshes(a.serve_requests, a.serve_fmax, a.serve_steps,
                                     workers=min(16, os.cpu_count() or 1))
 
@@ -470,7 +509,9 @@ def main():
         return
     tp.lib()
     if a.serve_only:
-        print(json.dumps(serving_bench(*serve_mesh, a.serve_steps, a.serve_fmax, verbose=True)), flush=True)
+        print(json.dumps(serving_bench(*serve_mesh, a.serve_steps, a.serve_fmax, verbose=True,
+                                       capacity_requests=a.serve_capacity_requests,
+                                       saturated=a.serve_saturated)), flush=True)
         return
     dev = torch.device("cuda", 0)
     mesh = mg.workload("torus40k")
@@ -609,9 +650,10 @@ def main():
         "descent_step": dstep,
     }
     P.close()
-    if a.serve_requests > 0:
-        out["serving"] = serving_bench(*serving_meshes(a.serve_requests, a.serve_fmax, a.serve_steps),
-                                       a.serve_steps, a.serve_fmax)
+    if serve_mesh is not None:
+        out["serving"] = serving_bench(*serve_mesh, a.serve_steps, a.serve_fmax, verbose=True,
+                                       capacity_requests=a.serve_capacity_requests,
+                                       saturated=a.serve_saturated)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, u_np, a.cpu_seconds)
         out["cpu_baseline"].update(cpu_info())

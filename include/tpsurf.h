@@ -92,6 +92,15 @@ typedef struct {
                             Barnes-Hut approximation of Sec. 4 with opening parameter
                             theta (the paper's default is 0.5), see tp_problem_bh_stats  */
     int    leaf_size;    /* faces per Barnes-Hut leaf, 1..64, default 8 (Sec. 4.1)       */
+    double chi;          /* 0 (default): the fractional operator's kernel sums directly
+                            (or by Barnes-Hut when theta > 0); > 0: by the block cluster
+                            tree and hierarchical multiplication of Sec. 5.1.4-5.1.5 with
+                            separation parameter chi (the paper's default is 0.5) on the
+                            Barnes-Hut tree: node pairs with max(r_I, r_J) < chi
+                            dist(box_I, box_J) are rank-one blocks k(X_I, X_J), leaf pairs
+                            that are not separated are exact (App. B: upward pass of node
+                            sums, far-field products per node, downward pass to faces);
+                            see tp_problem_bct_stats                                     */
 } tp_params;
 
 /* Fill *p with the defaults above. */
@@ -202,6 +211,17 @@ TP_API tp_status tp_problem_set_obstacle(tp_problem* prob, const double* Vo, int
 /* E_out = E_obs (unweighted) at the current vertices; dE_out (device nV x 3, or NULL) its
  * differential with respect to the surface's vertex positions. */
 TP_API tp_status tp_problem_obstacle_energy(tp_problem* prob, double* E_out, double* dE_out);
+
+/* Vertex pin constraints (Sec. 7.1.2): the vertices idx[0..n) (HOST int32 indices) keep
+ * their current positions in every later step.  Following Sec. 7.2 (linear positional
+ * rows go into the operator rather than the Schur complement), their rows are appended to
+ * both Laplacians of the preconditioner: each Poisson solve (of the step, and of
+ * tp_problem_poisson_solve / tp_problem_precond_apply) returns zero at the pinned vertices
+ * and solves C x = b on the other rows, and a component holding a pin has no mean-zero
+ * projection.  The direction and the corrective step therefore vanish at the pins.  n = 0
+ * removes all pins.  TP_E_BAD_INDEX for an index outside [0, nV); a step with pins and
+ * barycenter_motion = 1 or solver = 1 is TP_E_INVALID_ARGUMENT. */
+TP_API tp_status tp_problem_set_pins(tp_problem* prob, const int32_t* idx, int64_t n);
 
 /* Implicit obstacles and attractors (Sec. 7.3.3) on analytic signed distances d: kind 0 a
  * plane, d(x) = (q . x - c) / |q|; kind 1 a sphere, d(x) = |x - q| - c (c > 0 the radius;
@@ -377,10 +397,44 @@ TP_API tp_status tp_estimate_device_bytes(int64_t nV, int64_t nF, int max_degree
  * from X_S to a corner of S, r_I: from X_I = area-weighted barycenter to a corner of I's
  * box, dist: distance between the vertex boxes of S and I); admissible nodes contribute
  * K(X_S, N_S; X_I) a_S a_I, opened leaves their exact terms.  dE is the exact differential
- * of E_BH with the interaction lists held fixed (Sec. 4.2).  The fractional apply and the
- * Poisson solves are unchanged.  This call reports the numbers of far (node) and near
- * (face) terms of the problem's last Barnes-Hut evaluation. */
+ * of E_BH with the interaction lists held fixed (Sec. 4.2).  The fractional apply (every
+ * L^sigma product: tp_fractional_apply, the preconditioner, the step) uses the same tree
+ * and lists on the kernel matrix of Sec. 5.1.1: an admissible node I adds
+ * |X_S - X_I|^-(2 sigma + 2) (a_I ubar_S - sum_{T in I} a_T ubar_T), an opened leaf its exact
+ * terms (face sums only, deterministic).  The Poisson solves are unchanged.  This call
+ * reports the numbers of far (node) and near (face) terms of the problem's last
+ * Barnes-Hut energy evaluation. */
 TP_API tp_status tp_problem_bh_stats(tp_problem* prob, int64_t* far_terms, int64_t* near_terms);
+
+/* Numbers of admissible (rank-one) and inadmissible (exact leaf) blocks of the problem's
+ * last block cluster tree (params.chi > 0; zeros before the first hierarchical product). */
+TP_API tp_status tp_problem_bct_stats(tp_problem* prob, int64_t* admissible, int64_t* inadmissible);
+
+/* ----------------------------------------------------------------- remeshing */
+
+/* Dynamic remeshing (Sec. 6) of a triangle mesh between descent steps, on the host: one
+ * pass of edge splits (edges longer than 1.5 L0 at their midpoint), one pass of edge
+ * collapses (edges shorter than 0.5 L0 to their midpoint, refused where the link
+ * condition fails or a remaining face around either end would turn its normal over),
+ * then `iterations` rounds of Delaunay edge flips (interior edges whose opposite angles
+ * sum to more than pi; repeated sweeps, at most 64) each followed by one step of
+ * tangential smoothing: a vertex moves by rho times the area-weighted mean of (face
+ * circumcenter - vertex) over its faces, projected onto the plane orthogonal to its
+ * area-weighted normal; vertices on boundary edges stay.  Every choice follows the
+ * sorted order of the edges (as vertex pairs), so the result depends on the mesh alone.
+ * V: nV x 3 FP64 row-major, F: nF x 3 int32 (host memory, read only).  The result is
+ * written to V_out (cap_V x 3) and F_out (cap_F x 3), caller-owned host buffers, and its
+ * sizes to *nV_out, *nF_out; surviving vertices and faces keep their relative order and
+ * faces their orientation.  If a capacity is too small (or V_out / F_out is NULL) the
+ * sizes are still reported and TP_E_INVALID_ARGUMENT is returned: call again with room
+ * (nV + the number of edges longer than 1.5 L0, at most, before smoothing and flips).
+ * Errors: TP_E_INVALID_ARGUMENT (NULL inputs, nV < 3, nF < 1, L0 <= 0, iterations < 0,
+ * rho outside [0, 1)), TP_E_BAD_INDEX (face index outside [0, nV)), TP_E_NONFINITE
+ * (non-finite coordinates).  No device work; thread-safe.  The mesh's problem (its
+ * incidence, sparsity and trees) is rebuilt by creating a new tp_problem from the result. */
+TP_API tp_status tp_remesh(const double* V, int64_t nV, const int32_t* F, int64_t nF, double L0, int iterations,
+                           double rho, double* V_out, int64_t cap_V, int32_t* F_out, int64_t cap_F,
+                           int64_t* nV_out, int64_t* nF_out);
 
 /* ------------------------------------------------------------------- diagnostics */
 

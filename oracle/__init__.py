@@ -59,6 +59,10 @@ def lib():
         L.tpo_bh_frozen.argtypes = [_dp, _dp, i64, _ip, i64, d, d, d, ctypes.c_int, _dp, _lp]
         L.tpo_bh_frozen.restype = d
         L.tpo_bh_order.argtypes = [_dp, _ip, i64, ctypes.c_int, _lp]
+        L.tpo_bh_fractional.argtypes = [_dp, i64, _ip, i64, d, d, ctypes.c_int, _dp, ctypes.c_int, _dp]
+        L.tpo_bh_fractional.restype = ctypes.c_int
+        L.tpo_bct_fractional.argtypes = [_dp, i64, _ip, i64, d, d, ctypes.c_int, _dp, ctypes.c_int, _dp, _lp]
+        L.tpo_bct_fractional.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -388,17 +392,31 @@ def project_mean_zero(x, labels, ncomp=None):
     return x
 
 
-def poisson_solve(C, b, labels):
+def poisson_solve(C, b, labels, pins=None):
     """Exact solution x of C x = P b with P x = x (per-component mean zero), by a sparse
-    direct solve of C bordered with one indicator row per component."""
+    direct solve of C bordered with one indicator row per component.
+
+    With pins (vertex indices, Sec. 7.1.2), their rows are appended to the Laplacian as in
+    Sec. 7.2: the bordered system [[C, E^T], [E, 0]] with one unit row e_i per pinned vertex
+    gives x_i = 0 there and C x = b on the other rows; a component holding a pin has no
+    nullspace left, so only the components without pins keep the mean-zero rows."""
     b = np.asarray(b, dtype=np.float64)
     B2 = b.reshape(b.shape[0], -1)
     nV = C.shape[0]
     ncomp = int(labels.max()) + 1
-    Bm = sp.coo_matrix((np.ones(nV), (labels, np.arange(nV))), shape=(ncomp, nV))
-    M = sp.bmat([[C, Bm.T], [Bm, None]], format="csc")
-    Pb = project_mean_zero(B2, labels, ncomp)
-    rhs = np.vstack([Pb, np.zeros((ncomp, B2.shape[1]))])
+    pins = np.unique(np.asarray([] if pins is None else pins, dtype=np.int64))
+    pinned_comp = np.zeros(ncomp, dtype=bool)
+    pinned_comp[labels[pins]] = True
+    free = np.nonzero(~pinned_comp)[0]
+    Bm = sp.coo_matrix((np.ones(nV), (labels, np.arange(nV))), shape=(ncomp, nV)).tocsr()[free]
+    Pm = sp.coo_matrix((np.ones(pins.size), (np.arange(pins.size), pins)), shape=(pins.size, nV)).tocsr()
+    E = sp.vstack([Bm, Pm]).tocsr()
+    M = sp.bmat([[C, E.T], [E, None]], format="csc")
+    Pb = B2.copy()
+    for c in free:
+        msk = labels == c
+        Pb[msk] -= Pb[msk].mean(axis=0)
+    rhs = np.vstack([Pb, np.zeros((E.shape[0], B2.shape[1]))])
     sol = spla.splu(M).solve(rhs)
     return sol[:nV].reshape(b.shape)
 
@@ -442,11 +460,12 @@ def volume_gradient(V, F):
 # ----------------------------------------------------------------------------------
 # Preconditioner (Sec. 5.2) and one projected descent step (Sec. 3, 5.3, 5.4).
 
-def precond_apply(V, F, b, sigma=None, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, C=None, labels=None):
+def precond_apply(V, F, b, sigma=None, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, C=None, labels=None, pins=None):
     """A~^{-1} b = C^+ P L^sigma C^+ P b, columnwise (Sec. 5.2).
 
     Readings: both Laplace-Beltrami factors are the weak cotan matrix C with no mass
-    matrix; C^+ P b is the per-component mean-zero solution of C x = P b."""
+    matrix; C^+ P b is the per-component mean-zero solution of C x = P b.  With pins, both
+    factors are the Laplacian with the pin rows appended (poisson_solve, Sec. 7.2)."""
     V, F = _prep(V, F)
     if sigma is None:
         sigma = preconditioner_sigma(alpha, beta)
@@ -454,9 +473,9 @@ def precond_apply(V, F, b, sigma=None, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, C
         C = cotan_laplacian(V, F)
     if labels is None:
         _, labels = components(F, V.shape[0])
-    y = poisson_solve(C, b, labels)
+    y = poisson_solve(C, b, labels, pins)
     z = fractional_apply(V, F, y, sigma)
-    return poisson_solve(C, z, labels)
+    return poisson_solve(C, z, labels, pins)
 
 
 @dataclass
@@ -482,7 +501,7 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
                  line_search=True, constrain_area=True, constrain_volume=True,
                  area_target=None, volume_target=None, inverse=None, area_penalty=0.0,
                  volume_penalty=0.0, obstacle_mesh=None, obstacle_p=6.0, obstacle_weight=0.0,
-                 barycenter_motion=False, implicit=None):
+                 barycenter_motion=False, implicit=None, pins=None):
     """One constrained descent step with A~^{-1} in place of A_3^{-1}, or with the map R -> Y
     given as `inverse` (for instance A_3^{-1} from dense_sobolev_inverse; Sec. 5.4).
 
@@ -500,8 +519,14 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     total.  obstacle_mesh = (Vo, Fo) with obstacle_weight > 0 adds weight x the obstacle
     potential (obstacle) to the objective in the same way.  barycenter_motion adds to x, per
     connected component, minus the vertex-area-weighted mean of g (Sec. 7.1.1; vertex area
-    = a third of the areas of the faces around the vertex)."""
+    = a third of the areas of the faces around the vertex).  pins (vertex indices) adds the
+    vertex pin constraints of Sec. 7.1.2 the way Sec. 7.2 prescribes for linear positional
+    rows: inside the operator rather than in the Schur complement, i.e. appended to both
+    Laplacians of the preconditioner (precond_apply), so every column of Y, and with it the
+    direction and the corrective step, vanishes at the pinned vertices."""
     V, F = _prep(V, F)
+    if pins is not None and len(pins) and (barycenter_motion or inverse is not None):
+        raise ValueError("pins combine with neither barycenter motions nor a given inverse")
     nV = V.shape[0]
     if sigma is None:
         sigma = preconditioner_sigma(alpha, beta)
@@ -536,7 +561,7 @@ def precond_step(V, F, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA, sigma=None, tau=N
     if constrain_volume:
         rows.append(volume_gradient(V, F)); targets.append(V0); fns.append(total_volume)
     R = np.concatenate([g] + rows, axis=1)           # nV x 3(1 + k)
-    Y = precond_apply(V, F, R, sigma, C=C, labels=labels) if inverse is None else inverse(R)
+    Y = precond_apply(V, F, R, sigma, C=C, labels=labels, pins=pins) if inverse is None else inverse(R)
     yg = Y[:, 0:3]
     k = len(rows)
     YJ = [Y[:, 3 + 3 * m: 6 + 3 * m] for m in range(k)]
@@ -687,3 +712,37 @@ def bh_order(V, F, leaf=8):
     out = np.empty(F.shape[0], dtype=np.int64)
     lib().tpo_bh_order(_d(V), _i(F), F.shape[0], int(leaf), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     return out
+
+
+def bh_fractional_apply(V, F, u, theta, sigma=None, leaf=8, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
+    """L^sigma u with the Barnes-Hut approximation of the fractional kernel matrix on the
+    tree of bh_gradient (tpo_bh_fractional); theta = 0 is fractional_apply."""
+    V, F = _prep(V, F)
+    if sigma is None:
+        sigma = preconditioner_sigma(alpha, beta)
+    u = np.asarray(u, dtype=np.float64)
+    vec = u.ndim == 1
+    U = np.ascontiguousarray(u.reshape(u.shape[0], -1))
+    Lu = np.empty_like(U)
+    if lib().tpo_bh_fractional(_d(V), V.shape[0], _i(F), F.shape[0], sigma, float(theta), int(leaf), _d(U),
+                               U.shape[1], _d(Lu)) != 0:
+        raise ValueError("k must be in [1, 64]")
+    return Lu[:, 0] if vec else Lu
+
+
+def bct_fractional_apply(V, F, u, chi, sigma=None, leaf=8, alpha=DEFAULT_ALPHA, beta=DEFAULT_BETA):
+    """L^sigma u by the block cluster tree and hierarchical multiplication of Sec. 5.1.4 and
+    5.1.5 (tpo_bct_fractional); chi = 0 is fractional_apply.  Returns (Lu, (admissible
+    blocks, inadmissible blocks))."""
+    V, F = _prep(V, F)
+    if sigma is None:
+        sigma = preconditioner_sigma(alpha, beta)
+    u = np.asarray(u, dtype=np.float64)
+    vec = u.ndim == 1
+    U = np.ascontiguousarray(u.reshape(u.shape[0], -1))
+    Lu = np.empty_like(U)
+    cnt = np.zeros(2, dtype=np.int64)
+    if lib().tpo_bct_fractional(_d(V), V.shape[0], _i(F), F.shape[0], sigma, float(chi), int(leaf), _d(U),
+                                U.shape[1], _d(Lu), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))) != 0:
+        raise ValueError("k must be in [1, 63]")
+    return (Lu[:, 0] if vec else Lu), (int(cnt[0]), int(cnt[1]))

@@ -851,6 +851,169 @@ EXPORT double tpo_bh_frozen(const double* V0, const double* V, int64_t nV, const
     return E;
 }
 
+/* L^sigma u with the Barnes-Hut approximation of Sec. 4.1 carried over to the kernel
+ * matrix of the fractional operator (Sec. 5.1.1), on the tree and interaction lists of
+ * tpo_bh_frozen (same admissibility, same traversal).  For face S the exact row
+ *   w(S) = a_S sum_{T != S} k(X_S, X_T) a_T (ubar_S - ubar_T),   k = |d|^-(2 sigma + 2),
+ * takes, for an admissible node I, the kernel at the node's barycenter for all its faces:
+ *   sum_{T in I} k(X_S, X_T) a_T (ubar_S - ubar_T)  ~  k(X_S, X_I) (a_I ubar_S - m_I),
+ *   m_I = sum_{T in I} a_T ubar_T   (sums in sorted order, children left then right),
+ * and a leaf that is not admissible adds its faces T != S exactly.  Then, as for the direct
+ * sums, (L u)_i = 2 sum_{S ni i} w(S) / 3.  theta = 0 gives the direct sum.  k <= 64. */
+EXPORT int tpo_bh_fractional(const double* V, int64_t nV, const int32_t* F, int64_t nF, double sigma,
+                             double theta, int leaf, const double* u, int k, double* Lu)
+{
+    if (k < 1 || k > 64) return 1;
+    double *X, *A, *ub;
+    fractional_prepare(V, F, nF, u, k, &X, &A, &ub);
+    bh_tree T;
+    bh_build(V, F, nF, X, A, leaf, &T);
+    const int64_t M = 2 * T.P;
+    double* mI = calloc(M * k, sizeof(double));
+    for (int64_t l = 0; l < T.P; ++l)
+        for (int64_t p = l * leaf; p < (l + 1) * leaf && p < nF; ++p) {
+            const int64_t t = T.order[p];
+            for (int c = 0; c < k; ++c) mI[(T.P + l) * k + c] += A[t] * ub[t * k + c];
+        }
+    for (int64_t node = T.P - 1; node >= 1; --node)
+        for (int c = 0; c < k; ++c) mI[node * k + c] = mI[2 * node * k + c] + mI[(2 * node + 1) * k + c];
+    const double expo = -(2.0 * sigma + 2.0) * 0.5;
+    double* w = calloc(nF * k, sizeof(double));
+#pragma omp parallel
+    {
+        int* kinds = NULL;
+        int64_t* ids = NULL;
+        int64_t cap = 0;
+        double acc[64];
+#pragma omp for schedule(dynamic, 8)
+        for (int64_t s = 0; s < nF; ++s) {
+            const int64_t n = bh_list(&T, s, theta, &kinds, &ids, &cap);
+            for (int c = 0; c < k; ++c) acc[c] = 0.0;
+            for (int64_t q = 0; q < n; ++q) {
+                const int far = kinds[q] == 0;
+                const int64_t id = ids[q];
+                const double* Y = far ? T.X + 3 * id : X + 3 * id;
+                double d0 = X[3 * s] - Y[0], d1 = X[3 * s + 1] - Y[1], d2 = X[3 * s + 2] - Y[2];
+                const double kv = pow(d0 * d0 + d1 * d1 + d2 * d2, expo);
+                for (int c = 0; c < k; ++c)
+                    acc[c] += far ? kv * (T.a[id] * ub[s * k + c] - mI[id * k + c])
+                                  : kv * A[id] * (ub[s * k + c] - ub[id * k + c]);
+            }
+            for (int c = 0; c < k; ++c) w[s * k + c] = A[s] * acc[c];
+        }
+        free(kinds);
+        free(ids);
+    }
+    tpo_fractional_gather(F, nF, nV, w, k, Lu);
+    free(w); free(mI); free(X); free(A); free(ub);
+    bh_free(&T);
+    return 0;
+}
+
+/* Block cluster tree and hierarchical multiplication (Sec. 5.1.4, 5.1.5) for the kernel
+ * matrix of the fractional operator, K_ST = (1 - delta_ST) k(X_S, X_T), k = |d|^-(2 sigma + 2).
+ * Clusters are the nodes of the tree of tpo_bh_frozen.  Two clusters (I, J) are a separated
+ * pair when max(r_I, r_J) < chi dist(I, J) (r: from the area-weighted barycenter to the
+ * farthest corner of the cluster's box; dist: between the two boxes, which contain the
+ * clusters' convex hulls -- reading: the same boxes as Barnes-Hut, strict inequality so that
+ * chi = 0 separates nothing).  Starting from (root, root), a pair that is not separated and
+ * not made of two leaves is split into the pairs of the children (all leaves lie at the
+ * same depth).  Admissible blocks (separated) are rank one, 1_I k(X_I, X_J) 1_J^T;
+ * inadmissible ones (two leaves, not separated) are exact.  With y = K~ x,
+ *   w(S) = a_S (ubar_S (K~ a)(S) - (K~ (a ubar))(S)),
+ * the kernel-matrix form of the fractional operator's row sums (Sec. 5.1.1), and
+ * (L u)_i = 2 sum_{S ni i} w(S) / 3.  The products are taken block by block from the
+ * definition (no upward / downward passes).  chi = 0 gives the direct sum.  k <= 64.
+ * counts[0] = admissible blocks, counts[1] = inadmissible blocks. */
+static double bct_sep(const bh_tree* T, int64_t I, int64_t J, double chi)
+{
+    double d2 = 0.0;
+    for (int m = 0; m < 3; ++m) {
+        double g1 = T->lo[3 * J + m] - T->hi[3 * I + m];
+        double g2 = T->lo[3 * I + m] - T->hi[3 * J + m];
+        double g = g1 > g2 ? g1 : g2;
+        if (g < 0.0) g = 0.0;
+        d2 += g * g;
+    }
+    double r2 = T->r2[I] > T->r2[J] ? T->r2[I] : T->r2[J];
+    return r2 < (chi * chi) * d2;
+}
+
+EXPORT int tpo_bct_fractional(const double* V, int64_t nV, const int32_t* F, int64_t nF, double sigma,
+                              double chi, int leaf, const double* u, int k, double* Lu, int64_t* counts)
+{
+    if (k < 1 || k > 63) return 1;
+    double *X, *A, *ub;
+    fractional_prepare(V, F, nF, u, k, &X, &A, &ub);
+    bh_tree T;
+    bh_build(V, F, nF, X, A, leaf, &T);
+    const int kk = k + 1;                       /* x = [a, a ubar] */
+    double* x = malloc(sizeof(double) * nF * kk);
+    double* y = calloc(nF * kk, sizeof(double));
+    for (int64_t t = 0; t < nF; ++t) {
+        x[t * kk] = A[t];
+        for (int c = 0; c < k; ++c) x[t * kk + 1 + c] = A[t] * ub[t * k + c];
+    }
+    const double expo = -(2.0 * sigma + 2.0) * 0.5;
+    /* blocks by a breadth-first split of (root, root) */
+    int64_t cap = 1024, n = 1, head = 0, nadm = 0, ninad = 0;
+    int64_t* qI = malloc(sizeof(int64_t) * cap);
+    int64_t* qJ = malloc(sizeof(int64_t) * cap);
+    qI[0] = 1; qJ[0] = 1;
+    double* xs = malloc(sizeof(double) * kk);
+    while (head < n) {
+        const int64_t I = qI[head], J = qJ[head];
+        ++head;
+        if (!(T.a[I] > 0.0) || !(T.a[J] > 0.0)) continue;
+        const int64_t lI0 = I >= T.P ? (I - T.P) * leaf : 0, lJ0 = J >= T.P ? (J - T.P) * leaf : 0;
+        if (bct_sep(&T, I, J, chi)) {
+            ++nadm;
+            /* y_S += k(X_I, X_J) sum_{T in J} x_T for S in I: faces of a cluster are the sorted
+             * positions [first, last) of its subtree */
+            int64_t depthI = 0, depthJ = 0, a = I, b = J;
+            while (a < T.P) { a *= 2; ++depthI; }
+            while (b < T.P) { b *= 2; ++depthJ; }
+            const int64_t I0 = (a - T.P) * leaf, I1 = (a - T.P + ((int64_t)1 << depthI)) * leaf;
+            const int64_t J0 = (b - T.P) * leaf, J1 = (b - T.P + ((int64_t)1 << depthJ)) * leaf;
+            double d0 = T.X[3 * I] - T.X[3 * J], d1 = T.X[3 * I + 1] - T.X[3 * J + 1], d2 = T.X[3 * I + 2] - T.X[3 * J + 2];
+            const double kv = pow(d0 * d0 + d1 * d1 + d2 * d2, expo);
+            for (int c = 0; c < kk; ++c) xs[c] = 0.0;
+            for (int64_t p = J0; p < J1 && p < nF; ++p)
+                for (int c = 0; c < kk; ++c) xs[c] += x[T.order[p] * kk + c];
+            for (int64_t p = I0; p < I1 && p < nF; ++p)
+                for (int c = 0; c < kk; ++c) y[T.order[p] * kk + c] += kv * xs[c];
+        } else if (I >= T.P) {          /* two leaves (same depth): exact block */
+            ++ninad;
+            for (int64_t p = lI0; p < lI0 + leaf && p < nF; ++p) {
+                const int64_t S = T.order[p];
+                for (int64_t q = lJ0; q < lJ0 + leaf && q < nF; ++q) {
+                    const int64_t t = T.order[q];
+                    if (t == S) continue;
+                    double d0 = X[3 * S] - X[3 * t], d1 = X[3 * S + 1] - X[3 * t + 1], d2 = X[3 * S + 2] - X[3 * t + 2];
+                    const double kv = pow(d0 * d0 + d1 * d1 + d2 * d2, expo);
+                    for (int c = 0; c < kk; ++c) y[S * kk + c] += kv * x[t * kk + c];
+                }
+            }
+        } else {
+            if (n + 4 > cap) {
+                cap *= 2;
+                qI = realloc(qI, sizeof(int64_t) * cap);
+                qJ = realloc(qJ, sizeof(int64_t) * cap);
+            }
+            for (int e = 0; e < 2; ++e)
+                for (int f = 0; f < 2; ++f) { qI[n] = 2 * I + e; qJ[n] = 2 * J + f; ++n; }
+        }
+    }
+    double* w = malloc(sizeof(double) * nF * k);
+    for (int64_t S = 0; S < nF; ++S)
+        for (int c = 0; c < k; ++c) w[S * k + c] = A[S] * (ub[S * k + c] * y[S * kk] - y[S * kk + 1 + c]);
+    tpo_fractional_gather(F, nF, nV, w, k, Lu);
+    if (counts) { counts[0] = nadm; counts[1] = ninad; }
+    free(w); free(x); free(y); free(xs); free(qI); free(qJ); free(X); free(A); free(ub);
+    bh_free(&T);
+    return 0;
+}
+
 /* The sorted face order of the tree (for checks of the build). */
 EXPORT void tpo_bh_order(const double* V, const int32_t* F, int64_t nF, int leaf, int64_t* order)
 {

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtpsurf.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["tp_pairs.hip", "tp_mesh.hip", "tp_cg.hip", "tp_pcg.hip", "tp_bh.hip", "tp_sobolev.hip", "tp_obstacle.hip", "tp_api.hip"]
+SOURCES = ["tp_pairs.hip", "tp_mesh.hip", "tp_cg.hip", "tp_pcg.hip", "tp_bh.hip", "tp_sobolev.hip", "tp_obstacle.hip", "tp_remesh.hip", "tp_api.hip"]
 ARCH = os.environ.get("TPSURF_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -278,6 +278,13 @@ struct tp_problem {
     DevBuf<int32_t> vf_off, vf_idx, tmp_i, tmp_j;
     DevBuf<int32_t> lap_off, lap_col, comp;
     DevBuf<double> lap_val, inv_count;
+    // vertex pins: mask, the solver's cotan values with the pinned rows and columns replaced
+    // by the identity, and the component weights of the mean-zero projection with the
+    // pinned components left out
+    DevBuf<int8_t> pin_mask;
+    DevBuf<double> lap_pin, inv_count_pin;
+    int64_t npins = 0;
+    std::vector<int32_t> comp_host;
     DevBuf<int32_t> ell_col;
     DevBuf<double> ell_val;
     int ell_w = 0;
@@ -323,6 +330,12 @@ struct tp_problem {
     DevBuf<double> R, Y, W1, W2, gbuf, dir, Vt, Vsave;
 
     // Barnes-Hut tree and work arrays (params.theta > 0)
+    DevBuf<double> bh_nm;   // node moments of the Barnes-Hut fractional apply [2P][k]
+    // block cluster tree (chi > 0): device CSR lists, far-field values [2P][k + 1], the
+    // geometry version they describe and their block counts
+    DevBuf<int32_t> bct_far_off, bct_far_col, bct_near_off, bct_near_col;
+    DevBuf<double> bct_yt;
+    int64_t bct_ver = -1, bct_nadm = 0, bct_ninad = 0;
     DevBuf<double> bh_flo, bh_fhi, bh_fr2, bh_box, bh_na, bh_nsx, bh_nX, bh_nlo, bh_nhi, bh_nr2, bh_gS, bh_eS,
         bh_accF, bh_accN;
     DevBuf<uint64_t> bh_kin, bh_kout;
@@ -356,7 +369,8 @@ struct tp_problem {
         size_t b = V.bytes() + F.bytes() + fx.bytes() + fl.bytes() + fn.bytes() + dx.bytes() + dn.bytes() +
                    flags.bytes();
         b += vf_off.bytes() + vf_idx.bytes() + tmp_i.bytes() + tmp_j.bytes() + lap_off.bytes() +
-             lap_col.bytes() + comp.bytes() + lap_val.bytes() + inv_count.bytes() + ell_col.bytes() +
+             lap_col.bytes() + comp.bytes() + lap_val.bytes() + inv_count.bytes() + pin_mask.bytes() +
+             lap_pin.bytes() + inv_count_pin.bytes() + ell_col.bytes() +
              ell_val.bytes();
         b += pcg_perm.bytes() + pcg_pcol.bytes() + pcg_bstart.bytes() + pcg_whole.bytes() + pcg_blk.bytes() +
              pcg_astart.bytes() + pcg_aob.bytes() + pcg_acomp.bytes() + pcg_abl_off.bytes() + pcg_abl.bytes() +
@@ -378,7 +392,8 @@ struct tp_problem {
         b += bh_flo.bytes() + bh_fhi.bytes() + bh_fr2.bytes() + bh_box.bytes() + bh_na.bytes() + bh_nsx.bytes() +
              bh_nX.bytes() + bh_nlo.bytes() + bh_nhi.bytes() + bh_nr2.bytes() + bh_gS.bytes() + bh_eS.bytes() +
              bh_accF.bytes() + bh_accN.bytes() + bh_kin.bytes() + bh_kout.bytes() + bh_tmp.bytes() +
-             bh_order.bytes() + bh_pos.bytes() + bh_counts.bytes();
+             bh_order.bytes() + bh_pos.bytes() + bh_counts.bytes() + bh_nm.bytes() + bct_far_off.bytes() +
+             bct_far_col.bytes() + bct_near_off.bytes() + bct_near_col.bytes() + bct_yt.bytes();
         b += ng_kin.bytes() + ng_kout.bytes() + ng_vin.bytes() + ng_vout.bytes() + ng_sfx.bytes() + ng_sfl.bytes() +
              ng_cell.bytes() + ng_tmp.bytes() + ng_prm.bytes();
         return b;
@@ -428,6 +443,7 @@ tp_status validate_params(const tp_params* in, tp_params& out, double& sigma)
     if (out.cg_precond != 0 && out.cg_precond != 1) return fail(TP_E_INVALID_ARGUMENT, "cg_precond must be 0 or 1");
     if (!(out.theta >= 0.0) || !std::isfinite(out.theta)) return fail(TP_E_INVALID_ARGUMENT, "theta must be finite and >= 0");
     if (out.leaf_size < 1 || out.leaf_size > 64) return fail(TP_E_INVALID_ARGUMENT, "leaf_size must lie in [1, 64]");
+    if (!(out.chi >= 0.0) || !std::isfinite(out.chi)) return fail(TP_E_INVALID_ARGUMENT, "chi must be finite and >= 0");
     sigma = out.sigma;
     if (sigma < 0.0) {
         const double s = (out.beta - 2.0) / out.alpha;   // s = 2 - 2/p when beta = 2 alpha
@@ -757,6 +773,7 @@ tp_status ensure_lap(tp_problem* P)
     TP_HIP(hipMemcpyAsync(P->comp.p, label.data(), sizeof(int32_t) * P->nV, hipMemcpyHostToDevice, s));
     TP_HIP(hipMemcpyAsync(P->inv_count.p, cnt.data(), sizeof(double) * nc, hipMemcpyHostToDevice, s));
     TP_HIP(hipStreamSynchronize(s));
+    P->comp_host = label;
     if (P->prm.cg_precond) TP_TRY(build_pcg(P, label, nc, hoff, hcol));
     P->have_lap = true;
     return TP_OK;
@@ -768,9 +785,17 @@ tp_status ensure_cotan(tp_problem* P)
     if (!P->cotan_valid) {
         TP_HIP(launch_cotan_values(P->V.p, P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->lap_off.p,
                                    P->lap_col.p, P->lap_val.p, P->stream));
-        TP_HIP(launch_csr_to_ell(P->nV, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->ell_w,
-                                 P->ell_col.p, P->ell_val.p, P->stream));
-        if (P->have_pcg) TP_HIP(launch_pcg_setup(P->pcg, P->V.p, P->lap_off.p, P->lap_val.p, P->stream));
+        // the solvers' matrix: the cotan values, with the pin rows appended (Sec. 7.2)
+        const double* sv = P->lap_val.p;
+        if (P->npins > 0) {
+            TP_TRY(P->lap_pin.ensure(std::max<int64_t>(P->nnz, 1), P->stream));
+            TP_HIP(launch_pin_values(P->nV, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->pin_mask.p, P->lap_pin.p,
+                                     P->stream));
+            sv = P->lap_pin.p;
+        }
+        TP_HIP(launch_csr_to_ell(P->nV, P->lap_off.p, P->lap_col.p, sv, P->ell_w, P->ell_col.p, P->ell_val.p,
+                                 P->stream));
+        if (P->have_pcg) TP_HIP(launch_pcg_setup(P->pcg, P->V.p, P->lap_off.p, sv, P->stream));
         P->cotan_valid = true;
     }
     return TP_OK;
@@ -870,6 +895,7 @@ tp_status ensure_bh(tp_problem* P)
     TP_TRY(P->bh_accF.ensure(4 * nF, s));
     TP_TRY(P->bh_accN.ensure(4 * M, s));
     TP_TRY(P->bh_counts.ensure(2, s));
+    TP_TRY(P->bh_nm.ensure((size_t)M * kMaxGroupCols, s));
     BhBuffers& b = P->bh;
     b.flo = P->bh_flo.p; b.fhi = P->bh_fhi.p; b.fr2 = P->bh_fr2.p; b.box = P->bh_box.p;
     b.keys_in = P->bh_kin.p; b.keys_out = P->bh_kout.p; b.sort_tmp = P->bh_tmp.p; b.sort_bytes = tb;
@@ -887,6 +913,86 @@ tp_status ensure_tree(tp_problem* P)
         TP_HIP(launch_bh_build(P->bh, P->fd_V, P->F.p, P->face_orig.p, P->nF, P->prm.leaf_size, P->fd, P->stream));
         P->bh_ver = P->geom_ver;
     }
+    return TP_OK;
+}
+
+// Block lists of the block cluster tree (Sec. 5.1.4) for the current geometry, built on the
+// host from the tree's node boxes, radii and areas: a breadth-first split of (root, root);
+// a pair of clusters is admissible when max(r_I^2, r_J^2) < chi^2 dist^2 (dist between the
+// boxes), otherwise it is split into its children's pairs until both are leaves (all
+// leaves lie at the same depth); empty clusters (padding) are dropped.
+tp_status ensure_bct(tp_problem* P)
+{
+    TP_TRY(ensure_tree(P));
+    if (P->bct_ver == P->geom_ver) return TP_OK;
+    hipStream_t s = P->stream;
+    int64_t Pl = 0;
+    const int64_t M = (int64_t)bh_node_count(P->nF, P->prm.leaf_size, &Pl);
+    std::vector<double> na(M), nlo(3 * M), nhi(3 * M), nr2(M);
+    TP_HIP(hipMemcpyAsync(na.data(), P->bh.na, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    TP_HIP(hipMemcpyAsync(nlo.data(), P->bh.nlo, sizeof(double) * 3 * M, hipMemcpyDeviceToHost, s));
+    TP_HIP(hipMemcpyAsync(nhi.data(), P->bh.nhi, sizeof(double) * 3 * M, hipMemcpyDeviceToHost, s));
+    TP_HIP(hipMemcpyAsync(nr2.data(), P->bh.nr2, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    TP_HIP(hipStreamSynchronize(s));
+    const double chi2 = P->prm.chi * P->prm.chi;
+    auto separated = [&](int64_t I, int64_t J) {
+        double d2 = 0.0;
+        for (int m = 0; m < 3; ++m) {
+            const double g1 = nlo[3 * J + m] - nhi[3 * I + m];
+            const double g2 = nlo[3 * I + m] - nhi[3 * J + m];
+            double g = g1 > g2 ? g1 : g2;
+            g = g < 0.0 ? 0.0 : g;
+            d2 = d2 + g * g;
+        }
+        const double r2 = nr2[I] > nr2[J] ? nr2[I] : nr2[J];
+        return r2 < chi2 * d2;
+    };
+    std::vector<std::vector<int32_t>> far(M), near(Pl);
+    std::vector<std::pair<int64_t, int64_t>> cur{{1, 1}}, next;
+    int64_t nadm = 0, ninad = 0;
+    while (!cur.empty()) {
+        next.clear();
+        for (const auto& pr : cur) {
+            const int64_t I = pr.first, J = pr.second;
+            if (!(na[I] > 0.0) || !(na[J] > 0.0)) continue;
+            if (separated(I, J)) {
+                far[I].push_back((int32_t)J);
+                ++nadm;
+            } else if (I >= Pl) {
+                near[I - Pl].push_back((int32_t)(J - Pl));
+                ++ninad;
+            } else {
+                for (int e = 0; e < 2; ++e)
+                    for (int f = 0; f < 2; ++f) next.emplace_back(2 * I + e, 2 * J + f);
+            }
+        }
+        cur.swap(next);
+    }
+    auto to_csr = [](const std::vector<std::vector<int32_t>>& rows, std::vector<int32_t>& off,
+                     std::vector<int32_t>& col) {
+        off.assign(rows.size() + 1, 0);
+        for (size_t r = 0; r < rows.size(); ++r) off[r + 1] = off[r] + (int32_t)rows[r].size();
+        col.clear();
+        col.reserve(off.back());
+        for (const auto& r : rows) col.insert(col.end(), r.begin(), r.end());
+        if (col.empty()) col.push_back(0);
+    };
+    std::vector<int32_t> foff, fcol, noff, ncol;
+    to_csr(far, foff, fcol);
+    to_csr(near, noff, ncol);
+    TP_TRY(P->bct_far_off.ensure(foff.size(), s));
+    TP_TRY(P->bct_far_col.ensure(fcol.size(), s));
+    TP_TRY(P->bct_near_off.ensure(noff.size(), s));
+    TP_TRY(P->bct_near_col.ensure(ncol.size(), s));
+    TP_TRY(P->bct_yt.ensure((size_t)M * (kMaxGroupCols + 1), s));
+    TP_HIP(hipMemcpyAsync(P->bct_far_off.p, foff.data(), sizeof(int32_t) * foff.size(), hipMemcpyHostToDevice, s));
+    TP_HIP(hipMemcpyAsync(P->bct_far_col.p, fcol.data(), sizeof(int32_t) * fcol.size(), hipMemcpyHostToDevice, s));
+    TP_HIP(hipMemcpyAsync(P->bct_near_off.p, noff.data(), sizeof(int32_t) * noff.size(), hipMemcpyHostToDevice, s));
+    TP_HIP(hipMemcpyAsync(P->bct_near_col.p, ncol.data(), sizeof(int32_t) * ncol.size(), hipMemcpyHostToDevice, s));
+    TP_HIP(hipStreamSynchronize(s));    // the host vectors go out of scope
+    P->bct_nadm = nadm;
+    P->bct_ninad = ninad;
+    P->bct_ver = P->geom_ver;
     return TP_OK;
 }
 
@@ -1083,27 +1189,49 @@ tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, in
         const int kc = std::min(kMaxGroupCols, k - c0);
         const int kp = (kc + 3) / 4 * 4;
         double pairs = 0;
+        std::vector<PairJob> direct;
         for (size_t m = 0; m < B.size(); ++m) {
             tp_problem* P = B[m];
             const PairPlan pl = plan_for(kKindFrac, prec, kc, P->nF, P->cap);
             TP_TRY(P->ub.ensure((size_t)P->cap * kp * esz, s));
-            TP_TRY(P->part.ensure((size_t)pl.n_split * kc * pl.irows, s));
-            TP_TRY(P->zbuf.ensure((size_t)kc * pl.irows, s));
+            TP_TRY(P->zbuf.ensure((size_t)kc * std::max<int64_t>(pl.irows, P->nF), s));
             // face averages of columns [c0, c0 + kc): a shifted pointer with stride ldu
             TP_HIP(launch_face_avg(P->F.p, P->nF, P->cap, u[m] + c0, ldu, kc, kp, prec, P->ub.p, s));
-            jobs[m] = make_pair_job(P->fd, pl, P->part.p, P->ub.p);
             plans[m] = pl;
+            if (P->prm.chi > 0.0) {
+                // block cluster tree: hierarchical product, the row sums straight into zbuf
+                TP_TRY(ensure_bct(P));
+                TP_TRY(P->bh_nm.ensure((size_t)bh_node_count(P->nF, P->prm.leaf_size, nullptr) * kc, s));
+                BctLists bl;
+                bl.far_off = P->bct_far_off.p; bl.far_col = P->bct_far_col.p;
+                bl.near_off = P->bct_near_off.p; bl.near_col = P->bct_near_col.p;
+                TP_HIP(launch_bct_frac(P->bh, bl, P->nF, P->prm.leaf_size, prec, P->sigma, P->fd, P->ub.p, kp, kc,
+                                       P->bh_nm.p, P->bct_yt.p, P->zbuf.p, pl.irows, s));
+                continue;
+            }
+            if (P->prm.theta > 0.0) {
+                // Barnes-Hut on the kernel matrix: the row sums straight into zbuf
+                TP_TRY(ensure_tree(P));
+                TP_TRY(P->bh_nm.ensure((size_t)bh_node_count(P->nF, P->prm.leaf_size, nullptr) * kc, s));
+                TP_HIP(launch_bh_frac(P->bh, P->nF, P->prm.leaf_size, P->prm.theta, prec, P->sigma, P->fd, P->ub.p, kp,
+                                      kc, P->bh_nm.p, P->zbuf.p, pl.irows, s));
+                continue;
+            }
+            TP_TRY(P->part.ensure((size_t)pl.n_split * kc * pl.irows, s));
+            jobs[m] = make_pair_job(P->fd, pl, P->part.p, P->ub.p);
+            direct.push_back(jobs[m]);
             pairs += (double)P->nF * (double)(P->nF - 1);
         }
-        {
+        if (!direct.empty()) {
             PairTimer t(kKindFrac, pairs, pairs * kc, s);
-            TP_HIP(launch_pairs_frac(jobs.data(), (int)jobs.size(), prec, B[0]->sigma, kc, s));
+            TP_HIP(launch_pairs_frac(direct.data(), (int)direct.size(), prec, B[0]->sigma, kc, s));
             t.stop();
         }
         for (size_t m = 0; m < B.size(); ++m) {
             tp_problem* P = B[m];
             const PairPlan& pl = plans[m];
-            TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, kc, pl.irows, P->nF, P->zbuf.p, pl.irows, s));
+            if (!(P->prm.theta > 0.0) && !(P->prm.chi > 0.0))
+                TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, kc, pl.irows, P->nF, P->zbuf.p, pl.irows, s));
             TP_HIP(launch_ut_gather(P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->fd, P->zbuf.p, pl.irows,
                                     kc, ldl, c0, Lu[m], s));
         }
@@ -1181,7 +1309,9 @@ tp_status enqueue_cg(const Batch& B, double* const* b, double* const* x, int k, 
         tp_problem* P = B[m];
         TP_TRY(ensure_cotan(P));
         TP_TRY(ensure_cg(P, k));
-        TP_HIP(launch_project_mean(b[m], k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
+        TP_HIP(launch_project_mean(b[m], k, k, P->nV, P->comp.p, P->npins ? P->inv_count_pin.p : P->inv_count.p,
+                                   P->ncomp, P->red.p, s));
+        if (P->npins) TP_HIP(launch_zero_pinned(b[m], k, k, P->nV, P->pin_mask.p, s));
         if (P->have_pcg && P->pcg_ml) ml.push_back(m);
         else (P->have_pcg ? pc : plain).push_back(m);
     }
@@ -1253,7 +1383,11 @@ tp_status enqueue_cg(const Batch& B, double* const* b, double* const* x, int k, 
     }
     for (size_t m = 0; m < B.size(); ++m) {
         tp_problem* P = B[m];
-        TP_HIP(launch_project_mean(x[m], k, k, P->nV, P->comp.p, P->inv_count.p, P->ncomp, P->red.p, s));
+        TP_HIP(launch_project_mean(x[m], k, k, P->nV, P->comp.p, P->npins ? P->inv_count_pin.p : P->inv_count.p,
+                                   P->ncomp, P->red.p, s));
+        // the pinned rows are exactly zero (the coarse correction of the preconditioner
+        // leaves rounding-level values there)
+        if (P->npins) TP_HIP(launch_zero_pinned(x[m], k, k, P->nV, P->pin_mask.p, s));
         TP_HIP(hipMemcpyAsync(P->hiters.p + which * kMaxCols, P->cg_iters.p, sizeof(int) * k,
                               hipMemcpyDeviceToHost, s));
         TP_HIP(hipMemcpyAsync(P->hrelres.p + which * kMaxCols, P->cg_relres.p, sizeof(double) * k,
@@ -2367,6 +2501,10 @@ tp_status run_step_batch(tp_problem* const* probs, int n, const tp_step_opts* op
             T.st = fail(TP_E_INVALID_ARGUMENT, "barycenter_motion must be 0 or 1");
             continue;
         }
+        if (T.P->npins > 0 && (T.o.barycenter_motion || T.o.solver != 0)) {
+            T.st = fail(TP_E_INVALID_ARGUMENT, "vertex pins combine with neither barycenter motions nor solver = 1");
+            continue;
+        }
         if (!(T.o.area_penalty >= 0.0) || !(T.o.volume_penalty >= 0.0)) {
             T.st = fail(TP_E_INVALID_ARGUMENT, "penalty weights must be >= 0");
             continue;
@@ -2409,7 +2547,7 @@ tp_status run_step_batch(tp_problem* const* probs, int n, const tp_step_opts* op
             const tp_problem* b = S[q].P;
             if (a->prm.precision == b->prm.precision && a->prm.alpha == b->prm.alpha &&
                 a->prm.beta == b->prm.beta && a->sigma == b->sigma && S[m].ncol == S[q].ncol &&
-                a->prm.theta == b->prm.theta && a->prm.leaf_size == b->prm.leaf_size &&
+                a->prm.theta == b->prm.theta && a->prm.leaf_size == b->prm.leaf_size && a->prm.chi == b->prm.chi &&
                 S[m].o.solver == S[q].o.solver) {
                 G.push_back(&S[q]);
                 done[q] = true;
@@ -2481,7 +2619,9 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
     // the Morton order of the faces is computed with them)
     {
         const double M = (double)bh_node_count(nF, prm.leaf_size, nullptr);
-        b += f * (176.0 + 56.0) + M * 144.0 + (double)bh_sort_temp_bytes(nF) + 64;
+        b += f * (176.0 + 56.0) + M * (144.0 + 8.0 * kMaxGroupCols) + (double)bh_sort_temp_bytes(nF) + 64;
+        // block cluster tree lists and far-field values (chi > 0; about 64 blocks per node)
+        if (prm.chi > 0.0) b += M * (8.0 * (kMaxGroupCols + 1) + 4.0 * 64 + 8.0);
     }
     // FP64 near-field grid
     if (prm.precision == TP_PREC_FP32_NEAR64) b += (double)near_grid_bytes(nF);
@@ -2567,6 +2707,7 @@ tp_status tp_params_default(tp_params* p)
     p->cg_precond = 1;
     p->theta = 0.0;
     p->leaf_size = 8;
+    p->chi = 0.0;
     return TP_OK;
 }
 
@@ -2995,6 +3136,50 @@ tp_status tp_energy_faces_noalloc(const double* X, const double* N, const double
     if (h.flags[kFlagDegenerate]) return fail(TP_E_DEGENERATE_FACE, "a face has zero area (its normal is undefined)");
     *E_out = h.E;
     if (!std::isfinite(h.E)) return fail(TP_E_NONFINITE, "non-finite energy (coincident face barycenters?)");
+    return TP_OK;
+}
+
+tp_status tp_problem_set_pins(tp_problem* P, const int32_t* idx, int64_t n)
+{
+    TP_TRY(bind(P));
+    if (n < 0 || (n > 0 && !idx)) return fail(TP_E_INVALID_ARGUMENT, "need n >= 0 pinned vertices (host indices)");
+    for (int64_t q = 0; q < n; ++q)
+        if (idx[q] < 0 || idx[q] >= P->nV) return fail(TP_E_BAD_INDEX, "a pinned vertex index lies outside [0, nV)");
+    TP_TRY(ensure_lap(P));
+    hipStream_t s = P->stream;
+    std::vector<int8_t> mask(P->nV, 0);
+    int64_t cnt = 0;
+    for (int64_t q = 0; q < n; ++q)
+        if (!mask[idx[q]]) {
+            mask[idx[q]] = 1;
+            ++cnt;
+        }
+    if (cnt > 0) {
+        std::vector<double> w(P->ncomp, 0.0);
+        std::vector<char> pinned(P->ncomp, 0);
+        for (int64_t v = 0; v < P->nV; ++v) {
+            w[P->comp_host[v]] += 1.0;
+            if (mask[v]) pinned[P->comp_host[v]] = 1;
+        }
+        for (int c = 0; c < P->ncomp; ++c) w[c] = pinned[c] ? 0.0 : 1.0 / w[c];
+        TP_TRY(P->pin_mask.ensure(P->nV, s));
+        TP_TRY(P->inv_count_pin.ensure(P->ncomp, s));
+        TP_HIP(hipMemcpyAsync(P->pin_mask.p, mask.data(), (size_t)P->nV, hipMemcpyHostToDevice, s));
+        TP_HIP(hipMemcpyAsync(P->inv_count_pin.p, w.data(), sizeof(double) * P->ncomp, hipMemcpyHostToDevice, s));
+        TP_HIP(hipStreamSynchronize(s));
+    }
+    P->npins = cnt;
+    P->cotan_valid = false;     // the solvers' matrix changes
+    P->warm_cols = 0;
+    return TP_OK;
+}
+
+tp_status tp_problem_bct_stats(tp_problem* P, int64_t* admissible, int64_t* inadmissible)
+{
+    TP_TRY(bind(P));
+    if (!admissible || !inadmissible) return fail(TP_E_INVALID_ARGUMENT, "NULL argument");
+    *admissible = P->bct_nadm;
+    *inadmissible = P->bct_ninad;
     return TP_OK;
 }
 

@@ -396,6 +396,233 @@ __global__ void k_bh_assemble(int64_t nF, int leaf, int64_t P, const int32_t* __
     gface[6 * gstride + t] = ga;
 }
 
+// ---------------------------------------------------------------- fractional apply
+//
+// The kernel matrix of the fractional operator (Sec. 5.1.1) with the same tree, the same
+// admissibility and the same traversal as the energy: for face S an admissible node I adds
+// k(X_S, X_I) (a_I ubar_S - m_I), m_I = sum_{T in I} a_T ubar_T (the node's moments), a leaf
+// that is not admissible adds k(X_S, X_T) a_T (ubar_S - ubar_T) for its faces T != S, with
+// k = |d|^-(2 sigma + 2).  Only the face S side is summed, so there are no atomics and
+// the result is deterministic.  z(S) (without the factor a_S) goes to z[c * zstride + S],
+// the layout of the direct kernel's reduced sums.
+
+// Node moments, leaves first (member faces in sorted order), then level by level.
+template <class UB>
+__global__ void k_bh_moment_leaves(int64_t nF, int leaf, int64_t P, const int32_t* __restrict__ order,
+                                   const double4* __restrict__ dx, const UB* __restrict__ ub, int kp, int k,
+                                   double* __restrict__ nm)
+{
+    const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= P) return;
+    double acc[kMaxGroupCols];
+    for (int c = 0; c < kMaxGroupCols; ++c) acc[c] = 0.0;
+    for (int64_t p = l * leaf; p < (l + 1) * leaf && p < nF; ++p) {
+        const int32_t t = order[p];
+        const double a = dx[t].w;
+        for (int c = 0; c < k; ++c) acc[c] = acc[c] + a * (double)ub[(int64_t)t * kp + c];
+    }
+    for (int c = 0; c < k; ++c) nm[(P + l) * k + c] = acc[c];
+}
+
+__global__ __launch_bounds__(1024) void k_bh_moment_levels(int64_t P, int k, double* __restrict__ nm)
+{
+    for (int64_t n0 = P / 2; n0 >= 1; n0 /= 2) {
+        for (int64_t e = threadIdx.x; e < n0 * k; e += blockDim.x) {
+            const int64_t node = n0 + e / k;
+            const int c = (int)(e % k);
+            nm[node * k + c] = nm[2 * node * k + c] + nm[(2 * node + 1) * k + c];
+        }
+        __syncthreads();
+    }
+}
+
+template <class R>
+__device__ __forceinline__ double frac_kernel(const double (&xs)[3], const double* y, double expo)
+{
+    R d[3];
+    for (int m = 0; m < 3; ++m) d[m] = (R)(xs[m] - y[m]);
+    const R r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+    if (sizeof(R) == sizeof(float))
+        return (double)__builtin_amdgcn_exp2f((float)expo * __builtin_amdgcn_logf((float)r2));
+    return pow((double)r2, expo);
+}
+
+template <class R, class UB>
+__global__ __launch_bounds__(256) void k_bh_frac(BhArgs A, const UB* __restrict__ ub, int kp, int k,
+                                                 const double* __restrict__ nm, double expo,
+                                                 double* __restrict__ z, int64_t zstride)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= A.nF) return;
+    const int32_t s = A.order[p];
+    const double4 X = A.dx[s];
+    const double xs[3] = {X.x, X.y, X.z};
+    double slo[3], shi[3];
+    for (int m = 0; m < 3; ++m) {
+        slo[m] = A.flo[3 * s + m];
+        shi[m] = A.fhi[3 * s + m];
+    }
+    const double sr2 = A.fr2[s];
+    double us[kMaxGroupCols], acc[kMaxGroupCols];
+    for (int c = 0; c < kMaxGroupCols; ++c) {
+        us[c] = c < k ? (double)ub[(int64_t)s * kp + c] : 0.0;
+        acc[c] = 0.0;
+    }
+    int64_t node = 1;
+    for (;;) {
+        bool down = false;
+        if (A.na[node] > 0.0) {
+            if (admissible(A, slo, shi, sr2, node)) {
+                const double w = frac_kernel<R>(xs, A.nX + 3 * node, expo);
+                const double a = A.na[node];
+                for (int c = 0; c < k; ++c) acc[c] += w * (a * us[c] - nm[node * k + c]);
+            } else if (node >= A.P) {
+                const int64_t l = node - A.P;
+                const int64_t p1 = min((l + 1) * (int64_t)A.leaf, A.nF);
+                for (int64_t q = l * A.leaf; q < p1; ++q) {
+                    const int32_t t = A.order[q];
+                    if (t == s) continue;
+                    const double4 Y = A.dx[t];
+                    const double y[3] = {Y.x, Y.y, Y.z};
+                    const double w = frac_kernel<R>(xs, y, expo) * Y.w;
+                    for (int c = 0; c < k; ++c) acc[c] += w * (us[c] - (double)ub[(int64_t)t * kp + c]);
+                }
+            } else {
+                down = true;
+            }
+        }
+        if (down) {
+            node = 2 * node;
+            continue;
+        }
+        while (node & 1) node >>= 1;
+        if (node == 0) break;
+        node += 1;
+    }
+    for (int c = 0; c < k; ++c) z[c * zstride + s] = acc[c];
+}
+
+template <class UB>
+hipError_t bh_frac_launch(const BhBuffers& b, int64_t nF, int leaf, double theta, bool f64, const FaceData& fd,
+                          const UB* ub, int kp, int k, double expo, double* nm, double* z, int64_t zstride,
+                          hipStream_t s)
+{
+    int64_t P = 0;
+    (void)bh_node_count(nF, leaf, &P);
+    hipLaunchKernelGGL(k_bh_moment_leaves<UB>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, nF, leaf, P,
+                       b.order, fd.dx, ub, kp, k, nm);
+    hipLaunchKernelGGL(k_bh_moment_levels, dim3(1), dim3(1024), 0, s, P, k, nm);
+    BhArgs A;
+    A.nF = nF; A.P = P; A.leaf = leaf; A.theta2 = theta * theta; A.alpha = 0.0; A.beta = 0.0;
+    A.order = b.order; A.dx = fd.dx; A.dn = fd.dn; A.flo = b.flo; A.fhi = b.fhi; A.fr2 = b.fr2;
+    A.na = b.na; A.nX = b.nX; A.nlo = b.nlo; A.nhi = b.nhi; A.nr2 = b.nr2;
+    A.gS = nullptr; A.eS = nullptr; A.accF = nullptr; A.accN = nullptr; A.counts = nullptr;
+    const dim3 grid((unsigned)((nF + 255) / 256)), block(256);
+    if (f64) hipLaunchKernelGGL((k_bh_frac<double, UB>), grid, block, 0, s, A, ub, kp, k, nm, expo, z, zstride);
+    else hipLaunchKernelGGL((k_bh_frac<float, UB>), grid, block, 0, s, A, ub, kp, k, nm, expo, z, zstride);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- block cluster tree
+//
+// Hierarchical multiplication with the kernel matrix of the fractional operator (Sec.
+// 5.1.4, 5.1.5, App. B) on the same tree: the block lists (admissible node pairs grouped by
+// row node, inadmissible leaf pairs grouped by row leaf) are built on the host.  With
+// x = [a, a ubar] per face and its node sums x~_J = [a_J, m_J] (the upward pass: the
+// Barnes-Hut moments), y~_I = sum_{J admissible for I} k(X_I, X_J) x~_J (k_bct_far); face S
+// then adds the y~ of its leaf and all its ancestors (the downward pass, summed along the
+// face's path) and the exact terms of the leaves inadmissible for its own:
+//   z(S) = ubar_S Y0(S) - Y(S) + sum_{T in near leaves, T != S} k(X_S, X_T) a_T (ubar_S - ubar_T).
+
+template <class R>
+__device__ __forceinline__ double kern_pts(const double* x, const double* y, double expo)
+{
+    const double xs[3] = {x[0], x[1], x[2]};
+    return frac_kernel<R>(xs, y, expo);
+}
+
+template <class R>
+__global__ void k_bct_far(int64_t M, int k, const int32_t* __restrict__ off, const int32_t* __restrict__ col,
+                          const double* __restrict__ nX, const double* __restrict__ na,
+                          const double* __restrict__ nm, double expo, double* __restrict__ yt)
+{
+    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (I >= M) return;
+    double acc[kMaxGroupCols + 1];
+    for (int c = 0; c <= kMaxGroupCols; ++c) acc[c] = 0.0;
+    for (int32_t e = off[I]; e < off[I + 1]; ++e) {
+        const int32_t J = col[e];
+        const double w = kern_pts<R>(nX + 3 * I, nX + 3 * J, expo);
+        acc[0] += w * na[J];
+        for (int c = 0; c < k; ++c) acc[1 + c] += w * nm[(int64_t)J * k + c];
+    }
+    for (int c = 0; c <= k; ++c) yt[I * (k + 1) + c] = acc[c];
+}
+
+template <class R, class UB>
+__global__ __launch_bounds__(256) void k_bct_faces(int64_t nF, int leaf, int64_t P, const int32_t* __restrict__ order,
+                                                   const double4* __restrict__ dx, const UB* __restrict__ ub, int kp,
+                                                   int k, const int32_t* __restrict__ noff,
+                                                   const int32_t* __restrict__ ncol, const double* __restrict__ yt,
+                                                   double expo, double* __restrict__ z, int64_t zstride)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= nF) return;
+    const int32_t s = order[p];
+    const double4 X = dx[s];
+    const double xs[3] = {X.x, X.y, X.z};
+    double us[kMaxGroupCols], acc[kMaxGroupCols];
+    for (int c = 0; c < kMaxGroupCols; ++c) {
+        us[c] = c < k ? (double)ub[(int64_t)s * kp + c] : 0.0;
+        acc[c] = 0.0;
+    }
+    const int64_t L = p / leaf;
+    // near field: the leaves inadmissible for this face's leaf, in list order
+    for (int32_t e = noff[L]; e < noff[L + 1]; ++e) {
+        const int64_t J = ncol[e];
+        const int64_t q1 = min((J + 1) * (int64_t)leaf, nF);
+        for (int64_t q = J * leaf; q < q1; ++q) {
+            const int32_t t = order[q];
+            if (t == s) continue;
+            const double4 Y = dx[t];
+            const double y[3] = {Y.x, Y.y, Y.z};
+            const double w = frac_kernel<R>(xs, y, expo) * Y.w;
+            for (int c = 0; c < k; ++c) acc[c] += w * (us[c] - (double)ub[(int64_t)t * kp + c]);
+        }
+    }
+    // far field: the leaf's and its ancestors' y~, root last
+    double y0 = 0.0, yc[kMaxGroupCols];
+    for (int c = 0; c < kMaxGroupCols; ++c) yc[c] = 0.0;
+    for (int64_t node = P + L; node >= 1; node >>= 1) {
+        y0 += yt[node * (k + 1)];
+        for (int c = 0; c < k; ++c) yc[c] += yt[node * (k + 1) + 1 + c];
+    }
+    for (int c = 0; c < k; ++c) z[c * zstride + s] = acc[c] + (us[c] * y0 - yc[c]);
+}
+
+template <class UB>
+hipError_t bct_launch(const BhBuffers& b, const BctLists& bl, int64_t nF, int leaf, bool f64, const FaceData& fd,
+                      const UB* ub, int kp, int k, double expo, double* nm, double* yt, double* z, int64_t zstride,
+                      hipStream_t s)
+{
+    int64_t P = 0;
+    const int64_t M = (int64_t)bh_node_count(nF, leaf, &P);
+    hipLaunchKernelGGL(k_bh_moment_leaves<UB>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, nF, leaf, P,
+                       b.order, fd.dx, ub, kp, k, nm);
+    hipLaunchKernelGGL(k_bh_moment_levels, dim3(1), dim3(1024), 0, s, P, k, nm);
+    const dim3 gm((unsigned)((M + 255) / 256)), gf((unsigned)((nF + 255) / 256)), blk(256);
+    if (f64) {
+        hipLaunchKernelGGL(k_bct_far<double>, gm, blk, 0, s, M, k, bl.far_off, bl.far_col, b.nX, b.na, nm, expo, yt);
+        hipLaunchKernelGGL((k_bct_faces<double, UB>), gf, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
+                           bl.near_off, bl.near_col, yt, expo, z, zstride);
+    } else {
+        hipLaunchKernelGGL(k_bct_far<float>, gm, blk, 0, s, M, k, bl.far_off, bl.far_col, b.nX, b.na, nm, expo, yt);
+        hipLaunchKernelGGL((k_bct_faces<float, UB>), gf, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
+                           bl.near_off, bl.near_col, yt, expo, z, zstride);
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 size_t bh_node_count(int64_t nF, int leaf, int64_t* P_out)
@@ -480,4 +707,30 @@ hipError_t launch_bh_eval(const BhBuffers& b, int64_t nF, int leaf, double theta
     return hipGetLastError();
 }
 
+hipError_t launch_bh_frac(const BhBuffers& b, int64_t nF, int leaf, double theta, int precision, double sigma,
+                          const FaceData& fd, const void* ub, int kp, int k, double* nm, double* z, int64_t zstride,
+                          hipStream_t s)
+{
+    if (k < 1 || k > kMaxGroupCols) return hipErrorInvalidValue;
+    const double expo = -(sigma + 1.0);    // |d|^-(2 sigma + 2) = (|d|^2)^-(sigma + 1)
+    if (precision == TP_PREC_FP64)
+        return bh_frac_launch(b, nF, leaf, theta, true, fd, static_cast<const double*>(ub), kp, k, expo, nm, z,
+                              zstride, s);
+    return bh_frac_launch(b, nF, leaf, theta, false, fd, static_cast<const float*>(ub), kp, k, expo, nm, z, zstride,
+                          s);
+}
+
+hipError_t launch_bct_frac(const BhBuffers& b, const BctLists& bl, int64_t nF, int leaf, int precision,
+                           double sigma, const FaceData& fd, const void* ub, int kp, int k, double* nm, double* yt,
+                           double* z, int64_t zstride, hipStream_t s)
+{
+    if (k < 1 || k > kMaxGroupCols) return hipErrorInvalidValue;
+    const double expo = -(sigma + 1.0);
+    if (precision == TP_PREC_FP64)
+        return bct_launch(b, bl, nF, leaf, true, fd, static_cast<const double*>(ub), kp, k, expo, nm, yt, z, zstride,
+                          s);
+    return bct_launch(b, bl, nF, leaf, false, fd, static_cast<const float*>(ub), kp, k, expo, nm, yt, z, zstride, s);
+}
+
 }  // namespace tp
+

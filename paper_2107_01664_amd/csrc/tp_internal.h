@@ -190,6 +190,11 @@ hipError_t launch_project_mean(double* x, int ldx, int k, int64_t n, const int32
                                const double* inv_count, int ncomp, double* scratch,
                                hipStream_t s);
 size_t project_scratch_doubles(int k, int ncomp);
+// Vertex pins: the solver's copy of the cotan values with the pinned rows and columns
+// replaced by the identity; zeroing of the pinned rows of k columns.
+hipError_t launch_pin_values(int64_t n, const int32_t* off, const int32_t* col, const double* val,
+                             const int8_t* pinned, double* out, hipStream_t s);
+hipError_t launch_zero_pinned(double* x, int ldx, int k, int64_t n, const int8_t* pinned, hipStream_t s);
 
 // y = a*x + b*y style updates on n x 3 blocks: out = x + sum_m coef[m] * Y[:, cols_m].
 hipError_t launch_axpy_block3(int64_t n, const double* x, int ldx, double a,
@@ -235,6 +240,25 @@ hipError_t launch_bh_build(const BhBuffers& b, const double* V, const int32_t* F
 // ([7][gstride]: dE/dX, dE/dN, dE/da).
 hipError_t launch_bh_eval(const BhBuffers& b, int64_t nF, int leaf, double theta, int precision, double alpha,
                           double beta, const FaceData& fd, bool grad, double* gface, int64_t gstride,
+                          hipStream_t s);
+// L^sigma's kernel sums with Barnes-Hut (theta > 0) on the built tree: face averages ub
+// ([cap][kp], FP64 for TP_PREC_FP64 else FP32), node moments nm ([2P][k] doubles), output
+// z(S) (the row sums without a_S) at z[c * zstride + S], k <= kMaxGroupCols.
+// Block cluster tree of the fractional operator's kernel matrix (device CSR lists): per row
+// node the admissible column nodes, per row leaf the inadmissible column leaves.
+struct BctLists {
+    const int32_t* far_off = nullptr;    // [2P + 1]
+    const int32_t* far_col = nullptr;
+    const int32_t* near_off = nullptr;   // [P + 1] (leaf index = node - P)
+    const int32_t* near_col = nullptr;   // leaf indices
+};
+// L^sigma's kernel sums by hierarchical multiplication on the lists; nm [2P][k] node moments,
+// yt [2P][k + 1] far-field values, output as launch_bh_frac.
+hipError_t launch_bct_frac(const BhBuffers& b, const BctLists& bl, int64_t nF, int leaf, int precision,
+                           double sigma, const FaceData& fd, const void* ub, int kp, int k, double* nm, double* yt,
+                           double* z, int64_t zstride, hipStream_t s);
+hipError_t launch_bh_frac(const BhBuffers& b, int64_t nF, int leaf, double theta, int precision, double sigma,
+                          const FaceData& fd, const void* ub, int kp, int k, double* nm, double* z, int64_t zstride,
                           hipStream_t s);
 
 // Buffers of the near-field grid of one problem (device memory owned by the problem).

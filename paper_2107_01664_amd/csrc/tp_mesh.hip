@@ -805,4 +805,47 @@ hipError_t launch_copy_cols(int64_t n, const double* x, int ldx, int k, double* 
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ vertex pins
+//
+// Pinned vertices (Sec. 7.1.2) enter the Poisson solves as rows appended to the Laplacian
+// (Sec. 7.2): the bordered system's solution is zero at the pins and solves C x = b on the
+// other rows, which is the symmetric matrix with the pinned rows and columns replaced by
+// the identity and a zero right-hand side there.
+__global__ void k_pin_values(int64_t n, const int32_t* __restrict__ off, const int32_t* __restrict__ col,
+                             const double* __restrict__ val, const int8_t* __restrict__ pinned,
+                             double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const bool pi = pinned[i] != 0;
+    for (int32_t e = off[i]; e < off[i + 1]; ++e) {
+        const int32_t j = col[e];
+        out[e] = pi ? (j == i ? 1.0 : 0.0) : (pinned[j] ? 0.0 : val[e]);
+    }
+}
+
+hipError_t launch_pin_values(int64_t n, const int32_t* off, const int32_t* col, const double* val,
+                             const int8_t* pinned, double* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pin_values, dim3(nblocks(n)), dim3(256), 0, s, n, off, col, val, pinned, out);
+    return hipGetLastError();
+}
+
+__global__ void k_zero_pinned(double* __restrict__ x, int ldx, int k, int64_t n, const int8_t* __restrict__ pinned)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n * k) return;
+    const int64_t i = e / k;
+    if (pinned[i]) x[i * ldx + (e - i * k)] = 0.0;
+}
+
+hipError_t launch_zero_pinned(double* x, int ldx, int k, int64_t n, const int8_t* pinned, hipStream_t s)
+{
+    if (n <= 0 || k <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_pinned, dim3(nblocks(n * k)), dim3(256), 0, s, x, ldx, k, n, pinned);
+    return hipGetLastError();
+}
+
 }  // namespace tp
+

@@ -1,32 +1,37 @@
 // Two-level additive Schwarz preconditioned CG for the cotan Poisson solves (Sec. 5.2).
 //
-// Unknowns are reordered by (connected component, Morton code of the vertex position) and
-// cut into blocks of at most kBS consecutive vertices, so every block is a compact patch
-// of the surface.  The preconditioner is
-//     M^{-1} r = sum_B R_B^T C_BB^{-1} R_B r  +  R_0^T C_0^+ R_0 r,
-// with C_BB the block's rows and columns of C (exact dense inverse, FP64) and C_0 the
-// Galerkin coarse matrix of the block indicator vectors (C_0[B][B'] = sum of the entries
-// of C between B and B').  A block that is a whole component, and the coarse matrix, are
-// singular on the per-component constants; they are made invertible by adding the rank-one
-// term (d / m) 1 1^T per component (d a diagonal scale, m its size), which leaves the action
-// on per-component mean-zero vectors equal to the pseudo-inverse.
+// Unknowns are reordered by (connected component, Morton code of the vertex position on
+// the component's bounding cube) and cut into blocks of at most kBS consecutive vertices,
+// so every block is a compact patch of the surface.  The preconditioner is
+//     M^{-1} r = sum_B R_B^T C_BB^{-1} R_B r  +  Phi C_0^{-1} Phi^T r,
+// with C_BB the block's rows and columns of C (dense inverse by register-tiled
+// Gauss-Jordan, stored in FP32) and Phi a linear coarse space: aggregates of consecutive
+// blocks of one component, each carrying an orthonormalised basis of {1, x, y, z} centred
+// and scaled on the aggregate.  C_0 = Phi^T C Phi is assembled from per-row coarse weights;
+// per component the rank-one term d e e^T / (e^T e) (e the coefficients of the component's
+// constant, d the mean kept diagonal) makes it definite and leaves its action on
+// per-component mean-zero vectors equal to the pseudo-inverse.
 //
 // The solver is the Chronopoulos-Gear form of preconditioned CG: with u = M^{-1} r and
 // w = C u, the sums gamma = (r,u) and delta = (w,u) give beta = gamma / gamma_old and
 // alpha = gamma / (delta - beta gamma / alpha_old), and p = u + beta p, s = w + beta s (= C p),
-// x += alpha p, r -= alpha s.  One workgroup of kBS threads owns one block (one row per
-// thread) and keeps its C_BB^{-1} in LDS for the whole solve.  An iteration has two grid
-// exchanges (two-level counter barrier, bounded spin).  In the first, every block publishes
-// its block solve v = C_BB^{-1} r_B and the block sums of r (coarse right-hand side); after
-// it, every block forms the coarse values of its own and neighbouring blocks, u = v + c(block)
-// and C u from the neighbours' v.  In the second, the block partials of (r,u), (w,u) and
-// (r,r) are added.  All partial sums are added in block order by every workgroup, so every
-// workgroup takes the same decisions and the result does not depend on scheduling.  (The
-// pipelined form, which folds the sums into the next exchange, lost convergence here:
-// relative perturbations of 1e-15 per iteration in its auxiliary recurrences already cost
-// 15 % more iterations and 1e-13 stalled it, while this form is unchanged up to 1e-13.)
-// Every solve ends by checking the true residual b - C x and restarts from it when the
-// recursively updated residual has drifted.
+// x += alpha p, r -= alpha s.  One workgroup of 2 kBS threads owns one block (kBS row
+// owners and kBS helpers for the block product) and keeps C_BB^{-1} in LDS for the whole
+// solve.  An iteration has two grid exchanges through per-workgroup flag lines, the
+// exchanged values written and read as agent-scope atomics.  In the first, every block
+// publishes its block solve v = C_BB^{-1} r_B and its shares Phi_B^T r of the coarse
+// right-hand side; after it, every workgroup forms the coarse values of the aggregates its
+// rows touch, u = v + Phi c and C u from the neighbours' v.  In the second, the block
+// partials of (r,u), (w,u) and (r,r) are added.  All partial sums are added in block order
+// by every workgroup, so every workgroup takes the same decisions and the result does not
+// depend on scheduling.  (The pipelined form, which folds the sums into the next exchange,
+// lost convergence here: relative perturbations of 1e-15 per iteration in its auxiliary
+// recurrences already cost 15 % more iterations and 1e-13 stalled it, while this form is
+// unchanged up to 1e-13.)  A solve may start from a given x (warm start; the tolerance
+// stays relative to |b|).  Every solve ends by checking the true residual b - C x and
+// restarts from it when the recursively updated residual has drifted.  Problems with more
+// blocks than can be resident at once run the same iteration as one launch per phase
+// (k_ml_*, further below).
 #include "tp_solver.h"
 
 #include <algorithm>

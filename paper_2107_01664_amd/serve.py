@@ -117,9 +117,11 @@ def run(requests: Sequence[Request], executor, budget_bytes: int, max_active: in
 
     With small_faces None every admitted mesh takes part in every shared step.  With
     small_faces set, meshes with more faces form a second lane: rounds alternate between one
-    shared step of all admitted small meshes and one step of the next large mesh (round
-    robin), so a small mesh's step never waits for more than one large step.  Each lane
-    admits in arrival order (small meshes may overtake large ones); memory is shared.
+    shared step of all admitted small meshes and one step of the oldest admitted large mesh
+    (first come, first served within the lane, so a large request is not slowed down by the
+    large requests admitted after it), and a small mesh's step never waits for more than one
+    large step.  Each lane admits in arrival order (small meshes may overtake large ones);
+    memory is shared.
     """
     reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
     results = {r.rid: Result(r.rid, r.arrival, int(r.F.shape[0])) for r in reqs}
@@ -171,9 +173,7 @@ def run(requests: Sequence[Request], executor, budget_bytes: int, max_active: in
         turn = q + 1
         ln = lanes[q]
         if ln["one"]:
-            k = ln["rr"] % len(ln["active"])
-            ln["rr"] = k + 1
-            batch = [ln["active"][k]]
+            batch = [ln["active"][0]]          # the oldest admitted large mesh
         else:
             batch = list(ln["active"])
         sts, energies = executor.step([a[1] for a in batch])

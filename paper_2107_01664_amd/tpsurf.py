@@ -40,7 +40,8 @@ EXPORTED = [
     "tp_problem_precond_apply", "tp_step_opts_default",
     "tp_precond_step", "tp_last_error", "tp_profile_enable", "tp_profile_reset", "tp_profile_get",
     "tp_problem_poisson_solve", "tp_batch_step", "tp_problem_device_bytes",
-    "tp_estimate_device_bytes", "tp_problem_bh_stats", "tp_set_allocator",
+    "tp_estimate_device_bytes", "tp_problem_bh_stats", "tp_set_allocator", "tp_problem_set_pins",
+    "tp_problem_bct_stats", "tp_remesh",
 ]
 
 
@@ -53,7 +54,8 @@ class TpError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("precision", ctypes.c_int), ("cg_rtol", ctypes.c_double), ("cg_maxiter", ctypes.c_int),
-                ("cg_precond", ctypes.c_int), ("theta", ctypes.c_double), ("leaf_size", ctypes.c_int)]
+                ("cg_precond", ctypes.c_int), ("theta", ctypes.c_double), ("leaf_size", ctypes.c_int),
+                ("chi", ctypes.c_double)]
 
 
 class SolveReport(ctypes.Structure):
@@ -138,11 +140,14 @@ def lib() -> ctypes.CDLL:
         "tp_batch_step": [P(vp), i32, P(StepOpts), P(StepReport), P(i32)],
         "tp_problem_device_bytes": [vp, P(ctypes.c_uint64)],
         "tp_problem_bh_stats": [vp, P(i64), P(i64)],
+        "tp_problem_bct_stats": [vp, P(i64), P(i64)],
         "tp_estimate_device_bytes": [i64, i64, i32, i32, P(Params), i32, P(ctypes.c_uint64)],
         "tp_profile_enable": [i32],
         "tp_profile_reset": [],
         "tp_profile_get": [i32, P(KernelStats)],
         "tp_set_allocator": [ctypes.c_void_p, ctypes.c_void_p, vp],
+        "tp_problem_set_pins": [vp, P(i32), i64],
+        "tp_remesh": [vp, i64, vp, i64, d, i32, d, vp, i64, vp, i64, P(i64), P(i64)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -259,6 +264,31 @@ def tp_energy_faces_noalloc(X, N, a, params: Optional[Params] = None) -> float:
     _check(lib().tp_energy_faces_noalloc(X.data_ptr(), N.data_ptr(), a.data_ptr(), a.shape[0],
                                          ctypes.byref(params or default_params()), ctypes.byref(E), _stream()))
     return E.value
+
+
+def tp_remesh(V, F, L0: float, iterations: int = 5, rho: float = 0.5):
+    """Remesh on the host (splits, collapses, Delaunay flips, tangential smoothing).
+    V (nV, 3) and F (nF, 3) as numpy arrays or CPU tensors; returns new (V, F) numpy
+    arrays (float64, int32)."""
+    import numpy as np
+    V = np.ascontiguousarray(np.asarray(V.cpu() if isinstance(V, torch.Tensor) else V, dtype=np.float64))
+    F = np.ascontiguousarray(np.asarray(F.cpu() if isinstance(F, torch.Tensor) else F, dtype=np.int32))
+    if V.ndim != 2 or V.shape[1] != 3 or F.ndim != 2 or F.shape[1] != 3:
+        raise ValueError("V must be (nV, 3) and F (nF, 3)")
+    nv, nf = ctypes.c_int64(), ctypes.c_int64()
+    capV, capF = V.shape[0] + 3 * F.shape[0] // 2 + 16, 4 * F.shape[0] + 16
+    for _ in range(2):
+        Vo = np.empty((capV, 3), np.float64)
+        Fo = np.empty((capF, 3), np.int32)
+        st = lib().tp_remesh(V.ctypes.data, V.shape[0], F.ctypes.data, F.shape[0], float(L0), int(iterations),
+                             float(rho), Vo.ctypes.data, capV, Fo.ctypes.data, capF,
+                             ctypes.byref(nv), ctypes.byref(nf))
+        if st == 0:
+            return Vo[:nv.value].copy(), Fo[:nf.value].copy()
+        if nv.value <= capV and nf.value <= capF:
+            break
+        capV, capF = nv.value, nf.value
+    _check(st)
 
 
 def _cols(u, nV, name):
@@ -453,6 +483,18 @@ class Problem:
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().tp_problem_bh_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
         return int(a.value), int(b.value)
+
+    def bct_stats(self):
+        """(admissible, inadmissible) blocks of the last block cluster tree."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tp_problem_bct_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def set_pins(self, idx) -> None:
+        """Pin the listed vertices at their current positions (tp_problem_set_pins)."""
+        import numpy as np
+        a = np.ascontiguousarray(np.asarray(idx, dtype=np.int32).reshape(-1))
+        _check(lib().tp_problem_set_pins(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), a.size))
 
     def device_bytes(self) -> int:
         b = ctypes.c_uint64()

@@ -915,3 +915,38 @@ def test_step_warm_start(tp, meshes):
         assert abs(warm[s].tau - cold[s].tau) <= 1e-6 * cold[s].tau and warm[s].backtracks == cold[s].backtracks
         assert max(warm[s].cg_relres) <= 1e-10
     assert rel(Vw - m.V, Vc - m.V) <= 1e-7
+
+
+@pytest.mark.parametrize("name", ["small_sphere", "linked_small"])
+def test_step_vertex_pins(tp, meshes, name):
+    """Vertex pins (Sec. 7.1.2) as rows of the preconditioner's Laplacians (Sec. 7.2): the
+    pinned Poisson solve and the step at fixed tau against the oracle's, the pinned vertices
+    exactly in place after two steps; pins combine with neither barycenter motions nor
+    solver 1."""
+    m = meshes[name]
+    _, labels = O.components(m.F, m.nV)
+    pins = [3, 40] if name == "small_sphere" else [int(np.nonzero(labels == 0)[0][5])]
+    print(f"[parity] vertex pins {name} {pins}", flush=True)
+    b = mg.random_columns(m.nV, 3, 4)
+    C = O.cotan_laplacian(m.V, m.F)
+    x0 = O.poisson_solve(C, b, labels, pins)
+    tau = 2e-3
+    ref = O.precond_step(m.V, m.F, tau=tau, line_search=False, pins=pins)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        P.set_pins(pins)
+        x, _ = P.poisson_solve(dev(b))
+        d = torch.empty((m.nV, 3), dtype=torch.float64, device="cuda")
+        P.step(tp.step_opts(tau0=tau, line_search=0), direction=d)
+        V1 = P.vertices().cpu().numpy()
+        P.step()
+        V2 = P.vertices().cpu().numpy()
+        with pytest.raises(tp.TpError):
+            P.step(tp.step_opts(barycenter_motion=1))
+    x = x.cpu().numpy()
+    assert rel(x, x0) <= 1e-6 and np.abs(x[pins]).max() == 0.0
+    dd = d.cpu().numpy()
+    print("  direction error", rel(dd, ref.direction), flush=True)
+    assert rel(dd, ref.direction) <= 1e-4
+    assert np.abs(dd[pins]).max() == 0.0
+    assert rel(V1 - m.V, ref.V - m.V) <= 1e-4
+    assert np.array_equal(V1[pins], m.V[pins]) and np.array_equal(V2[pins], m.V[pins])

@@ -668,3 +668,54 @@ def test_implicit_obstacle_is_a_barrier(p):
     d_new = O.faces(r.V, m.F)[0][:, 2].min() - (zmin - 0.02)
     assert d_new > 0.0
     assert np.isfinite(O.implicit_potential(r.V, m.F, plane, False)[0])
+
+
+def test_vertex_pins():
+    """Vertex pins (Sec. 7.1.2) as rows appended to the Laplacians (Sec. 7.2).
+    1. The pinned Poisson solve is the Dirichlet problem: zero at the pins, C x = b on the
+       other rows (its definition), and the limit of the penalised solve (C + k E^T E) x = b
+       as k grows (a different method).
+    2. A step with pins: the direction vanishes at the pins and the pinned vertices keep
+       their positions exactly; the direction is still tangent to the area and volume rows
+       and a descent direction; on two components, a pin in one of them leaves the other
+       one's mean-zero convention in place."""
+    m = mg.add_noise(mg.icosphere(2), 0.02, 5)
+    V, F = m.V, m.F
+    C = O.cotan_laplacian(V, F)
+    _, labels = O.components(F, m.nV)
+    pins = [0, 17, 101]
+    b = np.random.default_rng(3).standard_normal((m.nV, 2))
+    x = O.poisson_solve(C, b, labels, pins)
+    free = np.setdiff1d(np.arange(m.nV), pins)
+    assert np.abs(x[pins]).max() == 0.0 or np.abs(x[pins]).max() <= 1e-14 * np.abs(x).max()
+    assert np.abs((C @ x - b)[free]).max() <= 1e-10 * np.abs(b).max()
+    E = sp_rows(m.nV, pins)
+    prev = None
+    for k in (1e4, 1e6, 1e8):
+        xk = np.linalg.solve((C + k * E.T @ E).toarray(), b)
+        err = np.abs(xk - x).max() / np.abs(x).max()
+        if prev is not None:
+            assert err < 0.05 * prev        # error falls like 1/k
+        prev = err
+    assert prev <= 1e-6
+    # the step
+    r = O.precond_step(V, F, tau=2e-3, line_search=False, pins=pins)
+    assert np.abs(r.direction[pins]).max() <= 1e-14 * np.abs(r.direction).max()
+    assert np.array_equal(r.V[pins], V[pins]) or np.abs(r.V[pins] - V[pins]).max() <= 1e-15
+    JA, JV = O.area_gradient(V, F), O.volume_gradient(V, F)
+    for J in (JA, JV):
+        assert abs(np.vdot(J, r.direction)) <= 1e-9 * np.linalg.norm(J) * np.linalg.norm(r.direction)
+    g = O.gradient(V, F)[1]
+    assert np.vdot(g, r.direction) < 0
+    two = mg.linked_tori(24, 12, 1.0, 0.25, 1.0)
+    _, lab2 = O.components(two.F, two.nV)
+    p2 = [int(np.nonzero(lab2 == 0)[0][3])]
+    r2 = O.precond_step(two.V, two.F, tau=2e-3, line_search=False, pins=p2)
+    assert np.abs(r2.direction[p2]).max() <= 1e-14 * np.abs(r2.direction).max()
+    y = O.poisson_solve(O.cotan_laplacian(two.V, two.F), np.ones((two.nV, 1)), lab2, p2)
+    assert abs(y[lab2 == 1].mean()) <= 1e-12          # the unpinned component stays mean-zero
+
+
+def sp_rows(n, idx):
+    import scipy.sparse as sp
+    return sp.coo_matrix((np.ones(len(idx)), (np.arange(len(idx)), idx)), shape=(len(idx), n)).tocsr()
