@@ -343,7 +343,10 @@ def sweep():
         F = torch.from_numpy(m.F).cuda()
         rows = {}
         ref = None
-        variants = [("fp64 direct", dict(precision=2)), ("fp32 direct, fp64 accumulation", dict(precision=1)),
+        variants = [("fp64 direct", dict(precision=2)),
+                    ("fp32 direct, fp32 accumulation (naive)", dict(precision=4)),
+                    ("fp32 direct, kahan fp32 accumulation", dict(precision=5)),
+                    ("fp32 direct, fp64 accumulation", dict(precision=1)),
                     ("fp32 hi/lo direct, fp64 accumulation", dict(precision=0)),
                     ("fp32 hi/lo direct + fp64 near field (default)", dict(precision=3)),
                     ("barnes-hut theta=0.5 fp32", dict(precision=0, theta=0.5)),

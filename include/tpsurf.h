@@ -63,17 +63,25 @@ typedef enum {
     TP_E_DEVICE = 8                  /* a HIP runtime error                             */
 } tp_status;
 
-/* Arithmetic of the all-pairs sums.  Accumulation is always FP64 per face. */
+/* Arithmetic of the all-pairs sums.  The terms of each 128-face tile are summed in FP32
+ * (FP64 for TP_PREC_FP64) and the per-face running sums are FP64, except in the two
+ * precision-sweep modes 4 and 5. */
 typedef enum {
     TP_PREC_FP32_HILO = 0,  /* FP32 pair terms; barycenter differences from hi+lo FP32
                                splits of the FP64 barycenters                             */
     TP_PREC_FP32 = 1,       /* FP32 pair terms from FP32-rounded barycenters              */
     TP_PREC_FP64 = 2,       /* FP64 pair terms                                            */
-    TP_PREC_FP32_NEAR64 = 3 /* as TP_PREC_FP32_HILO for the energy and its differential,
+    TP_PREC_FP32_NEAR64 = 3, /* as TP_PREC_FP32_HILO for the energy and its differential,
                                except that pairs whose barycenters are closer than twice
                                the mean edge length of the problem's first mesh (tested on
                                the FP32 hi+lo distance) are summed in FP64; the fractional
                                apply is as TP_PREC_FP32_HILO (default)                     */
+    TP_PREC_FP32_ACC32 = 4, /* as TP_PREC_FP32, with each face's running sum of E and dE
+                               terms over its j-split kept in FP32 (plain additions); the
+                               sums over splits, the chain rule and the total stay FP64.
+                               For precision studies only                                  */
+    TP_PREC_FP32_KAHAN = 5  /* as TP_PREC_FP32_ACC32 with Kahan's compensated summation of
+                               the per-face running sums. For precision studies only      */
 } tp_precision;
 
 typedef struct {
@@ -202,12 +210,22 @@ TP_API tp_status tp_problem_sobolev_apply(tp_problem* prob, const double* u, int
  * copied at the call) that repels the surface with the potential
  *   E_obs = sum_T a_T sum_{S in obstacle} a_O(S) |X_O(S) - X_T|^-p
  * (the obstacle potential of the paper evaluated at the barycenter of every face T of the
- * surface and integrated over T; FP64 direct sums, not Barnes-Hut).  With weight > 0 every
+ * surface and integrated over T; FP64).  With params.theta = 0 the sums are direct; with
+ * theta > 0 they use Barnes-Hut, as the end of Sec. 7.3.2 suggests: a tree over the
+ * obstacle's faces (the tree of the energy's Barnes-Hut, built once at this call), and for
+ * the barycenter X_T of each surface face, a point, node I is admissible when
+ * r_I^2 < theta^2 dist(X_T, box_I)^2 and then contributes a_I |X_I - X_T|^-p; leaves that
+ * are not admissible contribute face by face (see tp_problem_obstacle_stats).  With weight > 0 every
  * later descent step of this problem minimises E + weight E_obs (gradient, line search and
  * the report's energies).  nFo = 0 or weight = 0 removes the obstacle.  Errors:
  * TP_E_INVALID_ARGUMENT for bad sizes, indices, p <= 0 or weight < 0. */
 TP_API tp_status tp_problem_set_obstacle(tp_problem* prob, const double* Vo, int64_t nVo, const int32_t* Fo,
                                          int64_t nFo, double p, double weight);
+
+/* Term counts of the last obstacle evaluation: far (node) and near (face) terms summed over
+ * the surface's faces; with theta = 0, far = 0 and near = nF x nFo; both 0 without an
+ * obstacle. */
+TP_API tp_status tp_problem_obstacle_stats(tp_problem* prob, int64_t* far_terms, int64_t* near_terms);
 /* E_out = E_obs (unweighted) at the current vertices; dE_out (device nV x 3, or NULL) its
  * differential with respect to the surface's vertex positions. */
 TP_API tp_status tp_problem_obstacle_energy(tp_problem* prob, double* E_out, double* dE_out);

@@ -63,6 +63,8 @@ def lib():
         L.tpo_bh_fractional.restype = ctypes.c_int
         L.tpo_bct_fractional.argtypes = [_dp, i64, _ip, i64, d, d, ctypes.c_int, _dp, ctypes.c_int, _dp, _lp]
         L.tpo_bct_fractional.restype = ctypes.c_int
+        L.tpo_obstacle_bh.argtypes = [_dp, i64, _ip, i64, _dp, _ip, i64, d, d, ctypes.c_int, _dp, _lp]
+        L.tpo_obstacle_bh.restype = d
         _lib = L
     return _lib
 
@@ -619,6 +621,21 @@ def obstacle(V, F, Vo, Fo, p=6.0, with_grad=True):
     E = lib().tpo_obstacle(_d(V), V.shape[0], _i(F), F.shape[0], _d(Vo), _i(Fo), Fo.shape[0], p,
                            _d(dE) if with_grad else None)
     return float(E), dE
+
+
+def obstacle_bh(V, F, Vo, Fo, theta, p=6.0, leaf=8, with_grad=True):
+    """The static obstacle potential with Barnes-Hut over the obstacle's faces (tpo_obstacle_bh):
+    the tree of bh_gradient built on the obstacle, admissibility for the barycenter of each
+    surface face as a point.  Returns (E, dE or None, (far terms, near terms)); theta = 0 is
+    obstacle()."""
+    V, F = _prep(V, F)
+    Vo, Fo = _prep(Vo, Fo)
+    dE = np.empty_like(V) if with_grad else None
+    cnt = np.zeros(2, dtype=np.int64)
+    E = lib().tpo_obstacle_bh(_d(V), V.shape[0], _i(F), F.shape[0], _d(Vo), _i(Fo), Fo.shape[0], float(p),
+                              float(theta), int(leaf), _d(dE) if with_grad else None,
+                              cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return float(E), dE, (int(cnt[0]), int(cnt[1]))
 
 
 def implicit_potential(V, F, prims, with_grad=True):

@@ -1028,3 +1028,89 @@ EXPORT void tpo_bh_order(const double* V, const int32_t* F, int64_t nF, int leaf
     bh_free(&T);
     free(X); free(N); free(A); free(C);
 }
+
+/* Static obstacle potential by Barnes-Hut (Sec. 7.3.2, approximated as in Sec. 4.1).  The tree
+ * of bh_build over the obstacle's faces.  The potential is evaluated at the barycenter X_T of a
+ * surface face, a point without extent, so in the admissibility test of bh_admissible the
+ * target radius is zero: node I is admissible when r_I^2 < theta^2 dist(X_T, box_I)^2, and then
+ * contributes a_I |X_I - X_T|^-p; the faces of a leaf that is not admissible contribute one by
+ * one.  Nodes are visited depth first, left child first.  The differential is the exact one of
+ * this approximation with its lists held fixed; the obstacle does not move, so only the surface
+ * side exists and the chain rule is that of tpo_obstacle.  counts: far terms, near terms. */
+EXPORT double tpo_obstacle_bh(const double* V, int64_t nV, const int32_t* F, int64_t nF, const double* Vo,
+                              const int32_t* Fo, int64_t nFo, double p, double theta, int leaf, double* dE,
+                              int64_t* counts)
+{
+    double* XO = malloc(sizeof(double) * 3 * nFo);
+    double* NO = malloc(sizeof(double) * 3 * nFo);
+    double* AO = malloc(sizeof(double) * nFo);
+    double* CO = malloc(sizeof(double) * 3 * nFo);
+    all_faces(Vo, Fo, nFo, XO, NO, AO, CO);
+    bh_tree T;
+    bh_build(Vo, Fo, nFo, XO, AO, leaf, &T);
+    if (dE) memset(dE, 0, sizeof(double) * 3 * nV);
+    int64_t nfar = 0, nnear = 0;
+    double E = 0.0;
+    for (int64_t t = 0; t < nF; ++t) {
+        double X[3], N[3], a, c[3];
+        face_quantities(V, F, t, X, N, &a, c);
+        double phi = 0.0, g[3] = {0.0, 0.0, 0.0};
+        int64_t stack[128];
+        int sp = 0;
+        stack[sp++] = 1;
+        while (sp > 0) {
+            const int64_t node = stack[--sp];
+            if (!(T.a[node] > 0.0)) continue;
+            double d2 = 0.0;
+            for (int m = 0; m < 3; ++m) {
+                double g1 = T.lo[3 * node + m] - X[m], g2 = X[m] - T.hi[3 * node + m];
+                double gm = g1 > g2 ? g1 : g2;
+                if (gm < 0.0) gm = 0.0;
+                d2 += gm * gm;
+            }
+            const double* Y = NULL;
+            double w = 0.0;
+            if (T.r2[node] < (theta * theta) * d2) {
+                Y = T.X + 3 * node;
+                w = T.a[node];
+                ++nfar;
+            } else if (node >= T.P) {
+                const int64_t l = node - T.P;
+                for (int64_t q = l * T.leaf; q < (l + 1) * T.leaf && q < nFo; ++q) {
+                    const int64_t s = T.order[q];
+                    double d[3] = {X[0] - XO[3 * s], X[1] - XO[3 * s + 1], X[2] - XO[3 * s + 2]};
+                    double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+                    double ws = AO[s] * pow(r2, -0.5 * p);
+                    phi += ws;
+                    for (int m = 0; m < 3; ++m) g[m] += -p * ws / r2 * d[m];
+                    ++nnear;
+                }
+                continue;
+            } else {
+                stack[sp++] = 2 * node + 1;
+                stack[sp++] = 2 * node;
+                continue;
+            }
+            double d[3] = {X[0] - Y[0], X[1] - Y[1], X[2] - Y[2]};
+            double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+            double ws = w * pow(r2, -0.5 * p);
+            phi += ws;
+            for (int m = 0; m < 3; ++m) g[m] += -p * ws / r2 * d[m];
+        }
+        E += a * phi;
+        if (!dE) continue;
+        for (int corner = 0; corner < 3; ++corner) {
+            const double* fj = V + 3 * (int64_t)F[3 * t + (corner + 1) % 3];
+            const double* fk = V + 3 * (int64_t)F[3 * t + (corner + 2) % 3];
+            double e[3] = {fk[0] - fj[0], fk[1] - fj[1], fk[2] - fj[2]};
+            double da[3] = {0.5 * (N[1] * e[2] - N[2] * e[1]), 0.5 * (N[2] * e[0] - N[0] * e[2]),
+                            0.5 * (N[0] * e[1] - N[1] * e[0])};
+            int64_t i = F[3 * t + corner];
+            for (int m = 0; m < 3; ++m) dE[3 * i + m] += a * g[m] / 3.0 + phi * da[m];
+        }
+    }
+    if (counts) { counts[0] = nfar; counts[1] = nnear; }
+    bh_free(&T);
+    free(XO); free(NO); free(AO); free(CO);
+    return E;
+}

@@ -250,6 +250,50 @@ struct TabRing {
     }
 };
 
+// Barnes-Hut tree over a static obstacle's faces (built once, when the obstacle is set).
+struct ObsTree {
+    DevBuf<double> flo, fhi, fr2, box, na, nsx, nX, nlo, nhi, nr2;
+    DevBuf<uint64_t> kin, kout;
+    DevBuf<char> tmp;
+    DevBuf<int32_t> order, pos;
+    DevBuf<unsigned long long> counts;
+    BhBuffers view;
+    bool built = false;
+    size_t bytes() const
+    {
+        return flo.bytes() + fhi.bytes() + fr2.bytes() + box.bytes() + na.bytes() + nsx.bytes() + nX.bytes() +
+               nlo.bytes() + nhi.bytes() + nr2.bytes() + kin.bytes() + kout.bytes() + tmp.bytes() + order.bytes() +
+               pos.bytes() + counts.bytes();
+    }
+    tp_status ensure(int64_t nFo, int leaf, hipStream_t s)
+    {
+        const int64_t M = (int64_t)bh_node_count(nFo, leaf, nullptr);
+        TP_TRY(flo.ensure(3 * nFo, s));
+        TP_TRY(fhi.ensure(3 * nFo, s));
+        TP_TRY(fr2.ensure(nFo, s));
+        TP_TRY(box.ensure(6, s));
+        TP_TRY(kin.ensure(nFo, s));
+        TP_TRY(kout.ensure(nFo, s));
+        const size_t tb = bh_sort_temp_bytes(nFo);
+        TP_TRY(tmp.ensure(tb, s));
+        TP_TRY(order.ensure(nFo, s));
+        TP_TRY(pos.ensure(nFo, s));
+        TP_TRY(na.ensure(M, s));
+        TP_TRY(nsx.ensure(3 * M, s));
+        TP_TRY(nX.ensure(3 * M, s));
+        TP_TRY(nlo.ensure(3 * M, s));
+        TP_TRY(nhi.ensure(3 * M, s));
+        TP_TRY(nr2.ensure(M, s));
+        TP_TRY(counts.ensure(2, s));
+        BhBuffers& b = view;
+        b = BhBuffers();
+        b.flo = flo.p; b.fhi = fhi.p; b.fr2 = fr2.p; b.box = box.p; b.keys_in = kin.p; b.keys_out = kout.p;
+        b.sort_tmp = tmp.p; b.sort_bytes = tb; b.order = order.p; b.pos = pos.p; b.na = na.p; b.nsx = nsx.p;
+        b.nX = nX.p; b.nlo = nlo.p; b.nhi = nhi.p; b.nr2 = nr2.p; b.counts = counts.p;
+        return TP_OK;
+    }
+};
+
 }  // namespace tp
 
 using namespace tp;
@@ -323,6 +367,7 @@ struct tp_problem {
     ImplicitSet imp;
     int64_t obs_n = 0, obs_cap = 0;
     double obs_p = 6.0, obs_w = 0.0;
+    ObsTree obs_tree;               // Barnes-Hut tree of the obstacle (theta > 0)
     DevBuf<char> ub;
     DevBuf<double> cg_Z, cg_p, cg_red, cg_relres;
     DevBuf<unsigned> cg_bar;
@@ -379,7 +424,7 @@ struct tp_problem {
              pcg_rho.bytes() + pcg_red.bytes() + pcg_bp.bytes() + pcg_xp.bytes();
         b += gm_V.bytes() + gm_Z.bytes() + gm_w.bytes() + gm_b.bytes() + gm_r.bytes() + gm_x.bytes() +
              gm_small.bytes() + gm_red.bytes() + gm_Q.bytes() + gm_Qn.bytes() + gm_AQ.bytes() + gm_one.bytes() +
-             gm_lab0.bytes() + gm_dinv.bytes() + gm_sv.bytes() + gm_sw.bytes() + gm_smw.bytes() + obs_x.bytes() +
+             gm_lab0.bytes() + gm_dinv.bytes() + gm_sv.bytes() + gm_sw.bytes() + gm_smw.bytes() + obs_x.bytes() + obs_tree.bytes() +
              obs_e.bytes() + obs_g.bytes() + bm_area.bytes() + bm_t.bytes() + imp_e.bytes() + imp_g.bytes();
         b += ml_r.bytes() + ml_p.bytes() + ml_s.bytes() + ml_m.bytes() + ml_an.bytes() + ml_v.bytes() +
              ml_shares.bytes() + ml_g.bytes() + ml_part.bytes() + ml_state.bytes();
@@ -437,7 +482,7 @@ tp_status validate_params(const tp_params* in, tp_params& out, double& sigma)
         return fail(TP_E_INVALID_ARGUMENT, "alpha must be a finite number > 1");
     if (!(out.beta > 0.0) || !std::isfinite(out.beta))
         return fail(TP_E_INVALID_ARGUMENT, "beta must be a finite number > 0");
-    if (out.precision < 0 || out.precision > 3) return fail(TP_E_INVALID_ARGUMENT, "unknown precision");
+    if (out.precision < 0 || out.precision > 5) return fail(TP_E_INVALID_ARGUMENT, "unknown precision");
     if (!(out.cg_rtol > 0.0)) return fail(TP_E_INVALID_ARGUMENT, "cg_rtol must be > 0");
     if (out.cg_maxiter < 1) return fail(TP_E_INVALID_ARGUMENT, "cg_maxiter must be >= 1");
     if (out.cg_precond != 0 && out.cg_precond != 1) return fail(TP_E_INVALID_ARGUMENT, "cg_precond must be 0 or 1");
@@ -2037,7 +2082,11 @@ tp_status enqueue_obstacle(tp_problem* P)
     hipStream_t s = P->stream;
     TP_TRY(P->obs_e.ensure((size_t)P->nF, s));
     TP_TRY(P->obs_g.ensure((size_t)7 * P->nF, s));
-    TP_HIP(launch_obstacle_pairs(P->fd.dx, P->nF, P->obs_x.p, P->obs_cap, P->obs_p, P->obs_e.p, P->obs_g.p, P->nF, s));
+    if (P->obs_tree.built)
+        TP_HIP(launch_obstacle_bh(P->fd.dx, P->nF, P->obs_x.p, P->obs_tree.view, P->obs_n, P->prm.leaf_size,
+                                  P->prm.theta, P->obs_p, P->obs_e.p, P->obs_g.p, P->nF, P->obs_tree.counts.p, s));
+    else
+        TP_HIP(launch_obstacle_pairs(P->fd.dx, P->nF, P->obs_x.p, P->obs_cap, P->obs_p, P->obs_e.p, P->obs_g.p, P->nF, s));
     TP_HIP(launch_dot_cols(P->obs_e.p, 1, nullptr, 0, P->nF, 1, P->red.p, P->scal.p + kSlotObs, s));
     return TP_OK;
 }
@@ -2809,6 +2858,7 @@ tp_status tp_problem_set_obstacle(tp_problem* P, const double* Vo, int64_t nVo, 
     if (nFo == 0 || weight == 0.0) {   // remove the obstacle
         P->obs_n = 0;
         P->obs_w = 0.0;
+        P->obs_tree.built = false;
         return TP_OK;
     }
     if (!Vo || !Fo || nVo < 3 || nFo < 1) return fail(TP_E_INVALID_ARGUMENT, "obstacle needs Vo, Fo, nVo >= 3, nFo >= 1");
@@ -2822,8 +2872,19 @@ tp_status tp_problem_set_obstacle(tp_problem* P, const double* Vo, int64_t nVo, 
     for (int32_t v : fh)
         if (v < 0 || (int64_t)v >= nVo) return fail(TP_E_INVALID_ARGUMENT, "obstacle face index out of range");
     P->obs_cap = obstacle_capacity(nFo);
+    P->obs_tree.built = false;
     TP_TRY(P->obs_x.ensure((size_t)P->obs_cap, s));
     TP_HIP(launch_obstacle_faces(Vo, Fo, nFo, P->obs_cap, P->obs_x.p, s));
+    if (P->prm.theta > 0.0) {   // Barnes-Hut over the obstacle: its tree, once (the obstacle is static)
+        TP_TRY(P->obs_tree.ensure(nFo, P->prm.leaf_size, s));
+        FaceData fo;
+        fo.nF = nFo;
+        fo.cap = P->obs_cap;
+        fo.dx = P->obs_x.p;
+        TP_HIP(launch_bh_build(P->obs_tree.view, Vo, Fo, nullptr, nFo, P->prm.leaf_size, fo, s));
+        TP_HIP(hipMemsetAsync(P->obs_tree.counts.p, 0, 2 * sizeof(unsigned long long), s));
+        P->obs_tree.built = true;
+    }
     TP_HIP(hipStreamSynchronize(s));
     P->obs_n = nFo;
     P->obs_p = p;
@@ -3192,6 +3253,26 @@ tp_status tp_problem_bh_stats(tp_problem* P, int64_t* far_terms, int64_t* near_t
         TP_HIP(hipMemcpyAsync(h, P->bh_counts.p, sizeof(h), hipMemcpyDeviceToHost, P->stream));
         TP_HIP(hipStreamSynchronize(P->stream));
     }
+    *far_terms = (int64_t)h[0];
+    *near_terms = (int64_t)h[1];
+    return TP_OK;
+}
+
+tp_status tp_problem_obstacle_stats(tp_problem* P, int64_t* far_terms, int64_t* near_terms)
+{
+    TP_TRY(bind(P));
+    if (!far_terms || !near_terms) return fail(TP_E_INVALID_ARGUMENT, "NULL argument");
+    set_error("");
+    *far_terms = 0;
+    *near_terms = 0;
+    if (P->obs_n < 1) return TP_OK;
+    if (!P->obs_tree.built) {
+        *near_terms = P->nF * P->obs_n;
+        return TP_OK;
+    }
+    unsigned long long h[2] = {0, 0};
+    TP_HIP(hipMemcpyAsync(h, P->obs_tree.counts.p, sizeof(h), hipMemcpyDeviceToHost, P->stream));
+    TP_HIP(hipStreamSynchronize(P->stream));
     *far_terms = (int64_t)h[0];
     *near_terms = (int64_t)h[1];
     return TP_OK;

@@ -17,6 +17,13 @@ hipError_t launch_obstacle_faces(const double* Vo, const int32_t* Fo, int64_t nF
 hipError_t launch_obstacle_pairs(const double4* dx, int64_t nF, const double4* xo, int64_t cap_o, double p,
                                  double* e, double* g, int64_t gs, hipStream_t s);
 
+// The same potential and partials with Barnes-Hut over the obstacle (params.theta > 0): tree
+// = launch_bh_build over the obstacle faces (xo their face data, unpadded order), counts[2] =
+// far and near terms of this evaluation (cleared here).
+hipError_t launch_obstacle_bh(const double4* dx, int64_t nF, const double4* xo, const BhBuffers& tree, int64_t nFo,
+                              int leaf, double theta, double p, double* e, double* g, int64_t gs,
+                              unsigned long long* counts, hipStream_t s);
+
 // Implicit obstacles and attractors (Sec. 7.3.3) on analytic signed distances: kind 0 a plane,
 // d(x) = n . x - c (q = n, c), kind 1 a sphere, d(x) = |x - q| - c.  The potential of one
 // primitive is d^-p (obstacle) or |d|^p (attractor), weighted, evaluated at the face

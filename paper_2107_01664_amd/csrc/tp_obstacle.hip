@@ -67,6 +67,106 @@ __global__ __launch_bounds__(kBlock) void k_obs_pairs(const double4* __restrict_
     g[6 * gs + T] = phi;
 }
 
+// Barnes-Hut form (params.theta > 0): the tree of launch_bh_build over the obstacle's faces,
+// one thread per surface face, walked depth first (left child first) without a stack.  The
+// potential is evaluated at the barycenter X_T, a point, so node I is admissible when
+// r_I^2 < theta^2 dist(X_T, box_I)^2 (decided in FP64 without fused multiply-adds, so the
+// interaction lists are a function of the meshes alone) and then contributes
+// a_I |X_I - X_T|^-p; a leaf that is not admissible contributes its faces one by one.  Each
+// thread sums its own terms in traversal order; the term counts are integer atomics.
+struct ObsTreeArgs {
+    const double4* dx;        // surface face data (X_T, a_T)
+    int64_t nF;
+    const double4* xo;        // obstacle face data (X_O, a_O), caller's obstacle numbering
+    const int32_t* order;     // sorted position -> obstacle face
+    const double* na;
+    const double* nX;
+    const double* nlo;
+    const double* nhi;
+    const double* nr2;
+    int64_t nFo, P;
+    int leaf;
+    double theta2, p;
+    double* e;
+    double* g;
+    int64_t gs;
+    unsigned long long* counts;
+};
+
+__device__ __forceinline__ bool point_admissible(const ObsTreeArgs& A, const double4& x, int64_t node)
+{
+#pragma clang fp contract(off)
+    double d2 = 0.0;
+    const double xs[3] = {x.x, x.y, x.z};
+    for (int m = 0; m < 3; ++m) {
+        const double g1 = A.nlo[3 * node + m] - xs[m];
+        const double g2 = xs[m] - A.nhi[3 * node + m];
+        double gm = g1 > g2 ? g1 : g2;
+        gm = gm < 0.0 ? 0.0 : gm;
+        d2 = d2 + gm * gm;
+    }
+    return A.nr2[node] < A.theta2 * d2;
+}
+
+template <bool P6>
+__global__ __launch_bounds__(256) void k_obs_bh(ObsTreeArgs A)
+{
+    const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (T >= A.nF) return;
+    const double4 x = A.dx[T];
+    double phi = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+    unsigned long long nfar = 0, nnear = 0;
+    auto visit = [&](double yx, double yy, double yz, double w) {
+        const double d0 = x.x - yx, d1 = x.y - yy, d2 = x.z - yz;
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        const double inv = 1.0 / r2;
+        const double t = w * (P6 ? inv * inv * inv : pow(r2, -0.5 * A.p));
+        phi += t;
+        const double c = -A.p * t * inv;
+        g0 += c * d0;
+        g1 += c * d1;
+        g2 += c * d2;
+    };
+    int64_t node = 1;
+    for (;;) {
+        bool down = false;
+        if (A.na[node] > 0.0) {
+            if (point_admissible(A, x, node)) {
+                visit(A.nX[3 * node], A.nX[3 * node + 1], A.nX[3 * node + 2], A.na[node]);
+                ++nfar;
+            } else if (node >= A.P) {
+                const int64_t l = node - A.P;
+                const int64_t q1 = min((l + 1) * (int64_t)A.leaf, A.nFo);
+                for (int64_t q = l * A.leaf; q < q1; ++q) {
+                    const double4 o = A.xo[A.order[q]];
+                    visit(o.x, o.y, o.z, o.w);
+                    ++nnear;
+                }
+            } else {
+                down = true;
+            }
+        }
+        if (down) {
+            node = 2 * node;
+            continue;
+        }
+        while (node & 1) node >>= 1;      // climb out of right children (and the root)
+        if (node == 0) break;
+        node += 1;                        // right sibling
+    }
+    const int64_t gs = A.gs;
+    A.e[T] = x.w * phi;
+    A.g[T] = x.w * g0;
+    A.g[gs + T] = x.w * g1;
+    A.g[2 * gs + T] = x.w * g2;
+    A.g[3 * gs + T] = 0.0;
+    A.g[4 * gs + T] = 0.0;
+    A.g[5 * gs + T] = 0.0;
+    A.g[6 * gs + T] = phi;
+    atomicAdd(&A.counts[0], nfar);
+    atomicAdd(&A.counts[1], nnear);
+}
+
 __global__ void k_implicit(const double4* __restrict__ dx, int64_t nF, ImplicitSet set, double* __restrict__ e,
                            double* __restrict__ g, int64_t gs)
 {
@@ -175,6 +275,24 @@ hipError_t launch_obstacle_pairs(const double4* dx, int64_t nF, const double4* x
         hipLaunchKernelGGL(k_obs_pairs<true>, dim3(nblk(nF, kBlock)), dim3(kBlock), 0, s, dx, nF, xo, cap_o, p, e, g, gs);
     else
         hipLaunchKernelGGL(k_obs_pairs<false>, dim3(nblk(nF, kBlock)), dim3(kBlock), 0, s, dx, nF, xo, cap_o, p, e, g, gs);
+    return hipGetLastError();
+}
+
+hipError_t launch_obstacle_bh(const double4* dx, int64_t nF, const double4* xo, const BhBuffers& tree, int64_t nFo,
+                              int leaf, double theta, double p, double* e, double* g, int64_t gs,
+                              unsigned long long* counts, hipStream_t s)
+{
+    if (nF < 1 || nFo < 1 || gs < nF || leaf < 1) return hipErrorInvalidValue;
+    int64_t P = 0;
+    (void)bh_node_count(nFo, leaf, &P);
+    hipError_t err = hipMemsetAsync(counts, 0, 2 * sizeof(unsigned long long), s);
+    if (err != hipSuccess) return err;
+    ObsTreeArgs A;
+    A.dx = dx; A.nF = nF; A.xo = xo; A.order = tree.order; A.na = tree.na; A.nX = tree.nX; A.nlo = tree.nlo;
+    A.nhi = tree.nhi; A.nr2 = tree.nr2; A.nFo = nFo; A.P = P; A.leaf = leaf; A.theta2 = theta * theta; A.p = p;
+    A.e = e; A.g = g; A.gs = gs; A.counts = counts;
+    if (p == 6.0) hipLaunchKernelGGL(k_obs_bh<true>, dim3(nblk(nF)), dim3(256), 0, s, A);
+    else hipLaunchKernelGGL(k_obs_bh<false>, dim3(nblk(nF)), dim3(256), 0, s, A);
     return hipGetLastError();
 }
 

@@ -201,6 +201,40 @@ __device__ __forceinline__ bool tile_is_far(const float4& ilo, const float4& ihi
     return g2 >= (kFarRatio * kFarRatio) * (m * m);   // false for empty boxes (m = inf)
 }
 
+// ------------------------------------------------------------------ per-face accumulators
+//
+// What a face's running sum over the j-tiles of its split is kept in: FP64 (the library's
+// arithmetic), or, for the precision sweep only, plain FP32 or FP32 with Kahan's
+// compensated summation.  Each j-tile's 128 terms are summed in FP32 in every case; the
+// sums over splits, the chain rule to vertices and the energy total stay FP64.
+enum { kAcc64 = 0, kAcc32 = 1, kAccKahan = 2 };
+
+template <int ACC> struct FaceAcc;
+template <> struct FaceAcc<kAcc64> {
+    double s;
+    __device__ __forceinline__ void clear() { s = 0.0; }
+    __device__ __forceinline__ void add(float c) { s += (double)c; }
+    __device__ __forceinline__ double value() const { return s; }
+};
+template <> struct FaceAcc<kAcc32> {
+    float s;
+    __device__ __forceinline__ void clear() { s = 0.f; }
+    __device__ __forceinline__ void add(float c) { s += c; }
+    __device__ __forceinline__ double value() const { return (double)s; }
+};
+template <> struct FaceAcc<kAccKahan> {
+    float s, e;   // sum and the running error of its last additions (Kahan 1965)
+    __device__ __forceinline__ void clear() { s = 0.f; e = 0.f; }
+    __device__ __forceinline__ void add(float c)
+    {
+        const float y = c - e;
+        const float t = s + y;
+        e = (t - s) - y;
+        s = t;
+    }
+    __device__ __forceinline__ double value() const { return (double)s; }
+};
+
 // ============================================================== energy (FP32)
 
 // Squared FP32 distance of a pair, in one fixed sequence of operations (the FP64 near
@@ -243,7 +277,7 @@ __device__ __forceinline__ void energy_tile32(const float4* s_x, const float4* s
     }
 }
 
-template <int NI, bool HILO, bool NEAR, class Pow>
+template <int NI, bool HILO, bool NEAR, class Pow, int ACC = kAcc64>
 __global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
 {
     const PairJob J = pick_job(jb);
@@ -261,7 +295,7 @@ __global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
     const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
     float3 Sh[NI], Sl[NI], Sn[NI];
     int64_t Si[NI];
-    double acc[NI];
+    FaceAcc<ACC> acc[NI];
 #pragma unroll
     for (int r = 0; r < NI; ++r) {
         Si[r] = ibase + r * kBlock + threadIdx.x;
@@ -274,7 +308,7 @@ __global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
         } else {
             Sl[r] = make_float3(0.f, 0.f, 0.f);
         }
-        acc[r] = 0.0;
+        acc[r].clear();
     }
     float4 ilo, ihi;
     if (NEAR || HILO) irange_box(J.tbox, ibase, kBlock * NI, ilo, ihi);
@@ -295,10 +329,10 @@ __global__ __launch_bounds__(kBlock) void k_energy32(PairBatch jb, Pow pw)
         else
             energy_tile32<false, NI, HILO, false>(s_x, s_l, j0, Sh, Sl, Sn, Si, pw, J.rho2, c);
 #pragma unroll
-        for (int r = 0; r < NI; ++r) acc[r] += (double)c[r];
+        for (int r = 0; r < NI; ++r) acc[r].add(c[r]);
     }
 #pragma unroll
-    for (int r = 0; r < NI; ++r) part[(int64_t)bs * irows + Si[r]] = acc[r];
+    for (int r = 0; r < NI; ++r) part[(int64_t)bs * irows + Si[r]] = acc[r].value();
 }
 
 // ============================================================== energy + differential (FP32)
@@ -370,7 +404,7 @@ __device__ __forceinline__ void grad_tile32(const float4* s_x, const float4* s_l
     }
 }
 
-template <int NI, bool HILO, bool NEAR, class Pow>
+template <int NI, bool HILO, bool NEAR, class Pow, int ACC = kAcc64>
 __global__ __launch_bounds__(kBlock) void k_grad32(PairBatch jb, double alpha, double beta, Pow pw)
 {
     const PairJob J = pick_job(jb);
@@ -390,7 +424,7 @@ __global__ __launch_bounds__(kBlock) void k_grad32(PairBatch jb, double alpha, d
     const int jt1 = min(jt0 + tiles_per_split, ntiles_j);
     float3 Sh[NI], Sl[NI], Sn[NI];
     int64_t Si[NI];
-    double acc[NI][kGradAcc];
+    FaceAcc<ACC> acc[NI][kGradAcc];
 #pragma unroll
     for (int r = 0; r < NI; ++r) {
         Si[r] = ibase + r * kBlock + threadIdx.x;
@@ -404,7 +438,7 @@ __global__ __launch_bounds__(kBlock) void k_grad32(PairBatch jb, double alpha, d
             Sl[r] = make_float3(0.f, 0.f, 0.f);
         }
 #pragma unroll
-        for (int m = 0; m < kGradAcc; ++m) acc[r][m] = 0.0;
+        for (int m = 0; m < kGradAcc; ++m) acc[r][m].clear();
     }
     float4 ilo, ihi;
     if (NEAR || HILO) irange_box(J.tbox, ibase, kBlock * NI, ilo, ihi);
@@ -429,13 +463,15 @@ __global__ __launch_bounds__(kBlock) void k_grad32(PairBatch jb, double alpha, d
 #pragma unroll
         for (int r = 0; r < NI; ++r)
 #pragma unroll
-            for (int m = 0; m < kGradAcc; ++m) acc[r][m] += (double)c[r][m];
+            for (int m = 0; m < kGradAcc; ++m) acc[r][m].add(c[r][m]);
     }
 #pragma unroll
     for (int r = 0; r < NI; ++r) {
         const double aS = dxa[Si[r]].w;
         const double4 N = dn[Si[r]];
-        const double* a = acc[r];
+        double a[kGradAcc];
+#pragma unroll
+        for (int m = 0; m < kGradAcc; ++m) a[m] = acc[r][m].value();
         double out[kGradOut];
         out[0] = aS * (alpha * (N.x * a[0] + a[1]) - beta * a[4]);
         out[1] = aS * (alpha * (N.y * a[0] + a[2]) - beta * a[5]);
@@ -1052,6 +1088,12 @@ const void* energy_fn(int precision, bool p6)
     if (precision == TP_PREC_FP32_NEAR64)
         return p6 ? (const void*)k_energy32<kNiEnergy32, true, true, PowP6>
                   : (const void*)k_energy32<kNiEnergy32, true, true, PowGen>;
+    if (precision == TP_PREC_FP32_ACC32)
+        return p6 ? (const void*)k_energy32<kNiEnergy32, false, false, PowP6, kAcc32>
+                  : (const void*)k_energy32<kNiEnergy32, false, false, PowGen, kAcc32>;
+    if (precision == TP_PREC_FP32_KAHAN)
+        return p6 ? (const void*)k_energy32<kNiEnergy32, false, false, PowP6, kAccKahan>
+                  : (const void*)k_energy32<kNiEnergy32, false, false, PowGen, kAccKahan>;
     const bool hilo = precision == TP_PREC_FP32_HILO;
     if (p6) return hilo ? (const void*)k_energy32<kNiEnergy32, true, false, PowP6>
                         : (const void*)k_energy32<kNiEnergy32, false, false, PowP6>;
@@ -1066,6 +1108,12 @@ const void* grad_fn(int precision, bool p6)
     if (precision == TP_PREC_FP32_NEAR64)
         return p6 ? (const void*)k_grad32<kNiGrad32, true, true, PowP6>
                   : (const void*)k_grad32<kNiGrad32, true, true, PowGen>;
+    if (precision == TP_PREC_FP32_ACC32)
+        return p6 ? (const void*)k_grad32<kNiGrad32, false, false, PowP6, kAcc32>
+                  : (const void*)k_grad32<kNiGrad32, false, false, PowGen, kAcc32>;
+    if (precision == TP_PREC_FP32_KAHAN)
+        return p6 ? (const void*)k_grad32<kNiGrad32, false, false, PowP6, kAccKahan>
+                  : (const void*)k_grad32<kNiGrad32, false, false, PowGen, kAccKahan>;
     const bool hilo = precision == TP_PREC_FP32_HILO;
     if (p6) return hilo ? (const void*)k_grad32<kNiGrad32, true, false, PowP6>
                         : (const void*)k_grad32<kNiGrad32, false, false, PowP6>;
@@ -1185,6 +1233,12 @@ hipError_t launch_pairs_energy(const PairJob* jobs, int njobs, int precision, do
         } else if (precision == TP_PREC_FP32_NEAR64) {
             if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, true, PowP6>), grid, block, 0, s, jb, PowP6{});
             else hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, true, PowGen>), grid, block, 0, s, jb, g);
+        } else if (precision == TP_PREC_FP32_ACC32) {
+            if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, false, PowP6, kAcc32>), grid, block, 0, s, jb, PowP6{});
+            else hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, false, PowGen, kAcc32>), grid, block, 0, s, jb, g);
+        } else if (precision == TP_PREC_FP32_KAHAN) {
+            if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, false, PowP6, kAccKahan>), grid, block, 0, s, jb, PowP6{});
+            else hipLaunchKernelGGL((k_energy32<kNiEnergy32, false, false, PowGen, kAccKahan>), grid, block, 0, s, jb, g);
         } else if (precision == TP_PREC_FP32_HILO) {
             if (p6) hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, false, PowP6>), grid, block, 0, s, jb, PowP6{});
             else hipLaunchKernelGGL((k_energy32<kNiEnergy32, true, false, PowGen>), grid, block, 0, s, jb, g);
@@ -1208,6 +1262,12 @@ hipError_t launch_pairs_grad(const PairJob* jobs, int njobs, int precision, doub
         } else if (precision == TP_PREC_FP32_NEAR64) {
             if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, true, true, PowP6>), grid, block, 0, s, jb, alpha, beta, PowP6{});
             else hipLaunchKernelGGL((k_grad32<kNiGrad32, true, true, PowGen>), grid, block, 0, s, jb, alpha, beta, g);
+        } else if (precision == TP_PREC_FP32_ACC32) {
+            if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, false, false, PowP6, kAcc32>), grid, block, 0, s, jb, alpha, beta, PowP6{});
+            else hipLaunchKernelGGL((k_grad32<kNiGrad32, false, false, PowGen, kAcc32>), grid, block, 0, s, jb, alpha, beta, g);
+        } else if (precision == TP_PREC_FP32_KAHAN) {
+            if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, false, false, PowP6, kAccKahan>), grid, block, 0, s, jb, alpha, beta, PowP6{});
+            else hipLaunchKernelGGL((k_grad32<kNiGrad32, false, false, PowGen, kAccKahan>), grid, block, 0, s, jb, alpha, beta, g);
         } else if (precision == TP_PREC_FP32_HILO) {
             if (p6) hipLaunchKernelGGL((k_grad32<kNiGrad32, true, false, PowP6>), grid, block, 0, s, jb, alpha, beta, PowP6{});
             else hipLaunchKernelGGL((k_grad32<kNiGrad32, true, false, PowGen>), grid, block, 0, s, jb, alpha, beta, g);

@@ -7,9 +7,11 @@ built, loading fails with an error.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import math
 import os
+import weakref
 from dataclasses import dataclass
 from typing import Optional
 
@@ -25,7 +27,7 @@ STATUS_NAMES = {
     4: "TP_E_NONFINITE", 5: "TP_E_NOT_CONVERGED", 6: "TP_E_OUT_OF_MEMORY",
     7: "TP_E_SINGULAR_CONSTRAINTS", 8: "TP_E_DEVICE",
 }
-PREC_FP32_HILO, PREC_FP32, PREC_FP64, PREC_FP32_NEAR64 = 0, 1, 2, 3
+PREC_FP32_HILO, PREC_FP32, PREC_FP64, PREC_FP32_NEAR64, PREC_FP32_ACC32, PREC_FP32_KAHAN = 0, 1, 2, 3, 4, 5
 KIND_ENERGY, KIND_GRAD, KIND_FRAC, KIND_SOBOLEV = 0, 1, 2, 3
 
 # Every symbol the C-ABI exports (the header declares exactly these).
@@ -41,7 +43,7 @@ EXPORTED = [
     "tp_precond_step", "tp_last_error", "tp_profile_enable", "tp_profile_reset", "tp_profile_get",
     "tp_problem_poisson_solve", "tp_batch_step", "tp_problem_device_bytes",
     "tp_estimate_device_bytes", "tp_problem_bh_stats", "tp_set_allocator", "tp_problem_set_pins",
-    "tp_problem_bct_stats", "tp_remesh",
+    "tp_problem_bct_stats", "tp_remesh", "tp_problem_obstacle_stats",
 ]
 
 
@@ -141,6 +143,7 @@ def lib() -> ctypes.CDLL:
         "tp_problem_device_bytes": [vp, P(ctypes.c_uint64)],
         "tp_problem_bh_stats": [vp, P(i64), P(i64)],
         "tp_problem_bct_stats": [vp, P(i64), P(i64)],
+        "tp_problem_obstacle_stats": [vp, P(i64), P(i64)],
         "tp_estimate_device_bytes": [i64, i64, i32, i32, P(Params), i32, P(ctypes.c_uint64)],
         "tp_profile_enable": [i32],
         "tp_profile_reset": [],
@@ -345,6 +348,17 @@ def step_opts(**kw) -> StepOpts:
     return o
 
 
+_live_problems: "weakref.WeakSet[Problem]" = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_problems():
+    """Destroy problems still open when the interpreter exits, while the HIP runtime and
+    (with a registered allocator) the Python free callback are both still usable."""
+    for P in list(_live_problems):
+        P.close()
+
+
 class Problem:
     """Resident problem (tp_problem_*): topology, vertices and work buffers stay on the device."""
 
@@ -357,6 +371,7 @@ class Problem:
                                        ctypes.byref(params or default_params()), _stream(),
                                        ctypes.byref(h)))
         self._h = h
+        _live_problems.add(self)
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -488,6 +503,12 @@ class Problem:
         """(admissible, inadmissible) blocks of the last block cluster tree."""
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(lib().tp_problem_bct_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def obstacle_stats(self):
+        """(far, near) terms of the last obstacle evaluation (tp_problem_obstacle_stats)."""
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().tp_problem_obstacle_stats(self._h, ctypes.byref(a), ctypes.byref(b)))
         return a.value, b.value
 
     def set_pins(self, idx) -> None:

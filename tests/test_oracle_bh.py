@@ -137,3 +137,54 @@ def test_bct_fractional_apply():
     Lk, cnt = O.bct_fractional_apply(m.V, m.F, u, 0.5, sigma=-1.0)
     Ldk = O.fractional_apply(m.V, m.F, u, -1.0)
     assert cnt[0] > 0 and np.abs(Lk - Ldk).max() <= 1e-10 * np.abs(Ldk).max()
+
+
+def _obstacle_scene():
+    """A noisy sphere (320 faces) under a noisy torus obstacle (400 faces) 1.6 above it."""
+    m = mg.add_noise(mg.icosphere(2), 0.01, 1)
+    ob = mg.add_noise(mg.torus(20, 10, 0.6, 0.2), 0.01, 2)
+    return m, ob.V + np.array([0.0, 0.0, 1.6]), ob.F
+
+
+def test_obstacle_bh_limits():
+    """Barnes-Hut for the static obstacle (end of Sec. 7.3.2): theta = 0 is the direct sum
+    (every term a face term, nF x nFo of them); the error falls with theta; an obstacle far
+    away is one point mass at its area-weighted barycenter for every surface face (root node
+    admissible), checked against that closed form computed here from the face areas."""
+    m, Vo, Fo = _obstacle_scene()
+    E0, g0 = O.obstacle(m.V, m.F, Vo, Fo)
+    E, g, cnt = O.obstacle_bh(m.V, m.F, Vo, Fo, 0.0)
+    assert cnt == (0, m.nF * len(Fo))
+    assert abs(E - E0) <= 1e-13 * E0 and np.abs(g - g0).max() <= 1e-13 * np.abs(g0).max()
+    errs = []
+    for th in (0.25, 0.5, 1.0):
+        E, g, _ = O.obstacle_bh(m.V, m.F, Vo, Fo, th)
+        errs.append((abs(E - E0) / E0, np.linalg.norm(g - g0) / np.linalg.norm(g0)))
+    assert all(a[0] < b[0] and a[1] < b[1] for a, b in zip(errs, errs[1:])), errs
+    assert errs[1][0] < 0.02 and errs[1][1] < 0.02, errs
+    far = Vo + np.array([0.0, 0.0, 60.0])
+    E, _, cnt = O.obstacle_bh(m.V, m.F, far, Fo, 0.5)
+    assert cnt == (m.nF, 0)
+    Xo, _, ao = O.faces(far, Fo)
+    Y = (ao[:, None] * Xo).sum(0) / ao.sum()
+    X, _, a = O.faces(m.V, m.F)
+    Ec = float(np.sum(a * ao.sum() * np.linalg.norm(X - Y, axis=1) ** -6.0))
+    assert abs(E - Ec) <= 1e-12 * Ec
+
+
+def test_obstacle_bh_differential():
+    """dE of the Barnes-Hut obstacle potential against central differences of E_BH at
+    perturbations small enough to keep every interaction list (term counts unchanged)."""
+    m, Vo, Fo = _obstacle_scene()
+    _, g, cnt = O.obstacle_bh(m.V, m.F, Vo, Fo, 0.5)
+    rng = np.random.default_rng(4)
+    h = 1e-6
+    for v, c in zip(rng.integers(0, m.nV, 6), rng.integers(0, 3, 6)):
+        Vp, Vm = m.V.copy(), m.V.copy()
+        Vp[v, c] += h
+        Vm[v, c] -= h
+        Ep, _, cp = O.obstacle_bh(Vp, m.F, Vo, Fo, 0.5, with_grad=False)
+        Em, _, cm = O.obstacle_bh(Vm, m.F, Vo, Fo, 0.5, with_grad=False)
+        assert cp == cnt and cm == cnt
+        fd = (Ep - Em) / (2 * h)
+        assert abs(fd - g[v, c]) <= 1e-6 * np.abs(g).max(), (v, c, fd, g[v, c])
