@@ -16,15 +16,19 @@
 // (r_S: largest distance from X_S to a corner of S; dist: distance between the box of S's
 // vertices and the box of I).
 //
-// Traversal.  One thread per face, threads in Morton order so the lanes of a wave walk
-// similar paths.  An admissible node adds K(X_S, N_S; X_I) a_S a_I, a leaf that is not
-// admissible adds the exact terms of its faces T != S, other nodes are opened.  The
+// Traversal.  One thread per face, threads in Morton order, and the 64 lanes of a wave walk
+// the tree together (wave_walk): the wave visits the union of its lanes' lists in
+// depth-first order, each lane taking its own terms in the order of its own walk, and every
+// lane reads the same node at the same time.  An admissible node adds K(X_S, N_S; X_I)
+// a_S a_I, a leaf that is not admissible adds the exact terms of its faces T != S, other
+// nodes are opened.  The
 // differential is that of E_BH with the lists held fixed: the face S side is summed per
 // thread; the target side (dX, da of a face T or a node I) is added with device-scope
 // atomics; node derivatives then reach their member faces through X_I = sum a_T X_T / a_I
 // and a_I = sum a_T, walking up each face's ancestors.  The atomic sums make the last bits
 // of dE depend on scheduling; E itself is summed per face in a fixed order.
 #include "tp_internal.h"
+#include "tp_tree.h"
 
 #include <hipcub/hipcub.hpp>
 
@@ -289,8 +293,8 @@ template <class R, bool GEN, bool GRAD>
 __global__ __launch_bounds__(256) void k_bh_traverse(BhArgs A)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= A.nF) return;
-    const int32_t s = A.order[p];
+    const bool live = p < A.nF;                 // every lane walks with its wave
+    const int32_t s = A.order[live ? p : 0];
     const double4 X = A.dx[s], Nn = A.dn[s];
     const double xs[3] = {X.x, X.y, X.z}, ns[3] = {Nn.x, Nn.y, Nn.z};
     const double aS = X.w;
@@ -321,36 +325,25 @@ __global__ __launch_bounds__(256) void k_bh_traverse(BhArgs A)
         }
     };
 
-    int64_t node = 1;
-    for (;;) {
-        bool down = false;
-        if (A.na[node] > 0.0) {
-            if (admissible(A, slo, shi, sr2, node)) {
-                visit(A.nX + 3 * node, A.na[node], A.accN + node, 2 * A.P);
-                ++nfar;
-            } else if (node >= A.P) {
-                const int64_t l = node - A.P;
-                const int64_t p1 = min((l + 1) * (int64_t)A.leaf, A.nF);
-                for (int64_t q = l * A.leaf; q < p1; ++q) {
-                    const int32_t t = A.order[q];
-                    if (t == s) continue;
-                    const double4 Y = A.dx[t];
-                    const double y[3] = {Y.x, Y.y, Y.z};
-                    visit(y, Y.w, A.accF + t, A.nF);
-                    ++nnear;
-                }
-            } else {
-                down = true;
+    wave_walk(
+        A.na, A.P, live, [&](int node) { return admissible(A, slo, shi, sr2, node); },
+        [&](int node) {
+            visit(A.nX + 3 * (int64_t)node, A.na[node], A.accN + node, 2 * A.P);
+            ++nfar;
+        },
+        [&](int node) {
+            const int64_t l = node - A.P;
+            const int64_t p1 = min((l + 1) * (int64_t)A.leaf, A.nF);
+            for (int64_t q = l * A.leaf; q < p1; ++q) {
+                const int32_t t = A.order[q];
+                if (t == s) continue;
+                const double4 Y = A.dx[t];
+                const double y[3] = {Y.x, Y.y, Y.z};
+                visit(y, Y.w, A.accF + t, A.nF);
+                ++nnear;
             }
-        }
-        if (down) {
-            node = 2 * node;
-            continue;
-        }
-        while (node & 1) node >>= 1;      // climb out of right children (and the root)
-        if (node == 0) break;
-        node += 1;                        // right sibling
-    }
+        });
+    if (!live) return;
     A.eS[s] = e;
     if (GRAD) {
         for (int m = 0; m < 3; ++m) {
@@ -453,8 +446,8 @@ __global__ __launch_bounds__(256) void k_bh_frac(BhArgs A, const UB* __restrict_
                                                  double* __restrict__ z, int64_t zstride)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= A.nF) return;
-    const int32_t s = A.order[p];
+    const bool live = p < A.nF;                 // every lane walks with its wave
+    const int32_t s = A.order[live ? p : 0];
     const double4 X = A.dx[s];
     const double xs[3] = {X.x, X.y, X.z};
     double slo[3], shi[3];
@@ -464,42 +457,38 @@ __global__ __launch_bounds__(256) void k_bh_frac(BhArgs A, const UB* __restrict_
     }
     const double sr2 = A.fr2[s];
     double us[kMaxGroupCols], acc[kMaxGroupCols];
+#pragma unroll
     for (int c = 0; c < kMaxGroupCols; ++c) {
         us[c] = c < k ? (double)ub[(int64_t)s * kp + c] : 0.0;
         acc[c] = 0.0;
     }
-    int64_t node = 1;
-    for (;;) {
-        bool down = false;
-        if (A.na[node] > 0.0) {
-            if (admissible(A, slo, shi, sr2, node)) {
-                const double w = frac_kernel<R>(xs, A.nX + 3 * node, expo);
-                const double a = A.na[node];
-                for (int c = 0; c < k; ++c) acc[c] += w * (a * us[c] - nm[node * k + c]);
-            } else if (node >= A.P) {
-                const int64_t l = node - A.P;
-                const int64_t p1 = min((l + 1) * (int64_t)A.leaf, A.nF);
-                for (int64_t q = l * A.leaf; q < p1; ++q) {
-                    const int32_t t = A.order[q];
-                    if (t == s) continue;
-                    const double4 Y = A.dx[t];
-                    const double y[3] = {Y.x, Y.y, Y.z};
-                    const double w = frac_kernel<R>(xs, y, expo) * Y.w;
-                    for (int c = 0; c < k; ++c) acc[c] += w * (us[c] - (double)ub[(int64_t)t * kp + c]);
-                }
-            } else {
-                down = true;
+    wave_walk(
+        A.na, A.P, live, [&](int node) { return admissible(A, slo, shi, sr2, node); },
+        [&](int node) {
+            const double w = frac_kernel<R>(xs, A.nX + 3 * (int64_t)node, expo);
+            const double a = A.na[node];
+#pragma unroll
+            for (int c = 0; c < kMaxGroupCols; ++c)
+                if (c < k) acc[c] += w * (a * us[c] - nm[(int64_t)node * k + c]);
+        },
+        [&](int node) {
+            const int64_t l = node - A.P;
+            const int64_t p1 = min((l + 1) * (int64_t)A.leaf, A.nF);
+            for (int64_t q = l * A.leaf; q < p1; ++q) {
+                const int32_t t = A.order[q];
+                if (t == s) continue;
+                const double4 Y = A.dx[t];
+                const double y[3] = {Y.x, Y.y, Y.z};
+                const double w = frac_kernel<R>(xs, y, expo) * Y.w;
+#pragma unroll
+                for (int c = 0; c < kMaxGroupCols; ++c)
+                    if (c < k) acc[c] += w * (us[c] - (double)ub[(int64_t)t * kp + c]);
             }
-        }
-        if (down) {
-            node = 2 * node;
-            continue;
-        }
-        while (node & 1) node >>= 1;
-        if (node == 0) break;
-        node += 1;
-    }
-    for (int c = 0; c < k; ++c) z[c * zstride + s] = acc[c];
+        });
+    if (!live) return;
+#pragma unroll
+    for (int c = 0; c < kMaxGroupCols; ++c)
+        if (c < k) z[c * zstride + s] = acc[c];
 }
 
 template <class UB>
@@ -541,22 +530,109 @@ __device__ __forceinline__ double kern_pts(const double* x, const double* y, dou
     return frac_kernel<R>(xs, y, expo);
 }
 
+// Admissible blocks: one wave per row node I.  The lanes take the node's list in strides of
+// 64 entries; the k + 1 sums are then added across the wave in a fixed order (butterfly), so
+// the result does not depend on timing.
 template <class R>
-__global__ void k_bct_far(int64_t M, int k, const int32_t* __restrict__ off, const int32_t* __restrict__ col,
-                          const double* __restrict__ nX, const double* __restrict__ na,
-                          const double* __restrict__ nm, double expo, double* __restrict__ yt)
+__global__ __launch_bounds__(256) void k_bct_far(int64_t M, int k, const int32_t* __restrict__ off,
+                                                 const int32_t* __restrict__ col, const double* __restrict__ nX,
+                                                 const double* __restrict__ na, const double* __restrict__ nm,
+                                                 double expo, double* __restrict__ yt)
 {
-    const int64_t I = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (I >= M) return;
+    const int64_t I = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    if (I >= M) return;                       // the whole wave
     double acc[kMaxGroupCols + 1];
+#pragma unroll
     for (int c = 0; c <= kMaxGroupCols; ++c) acc[c] = 0.0;
-    for (int32_t e = off[I]; e < off[I + 1]; ++e) {
+    const double xi[3] = {nX[3 * I], nX[3 * I + 1], nX[3 * I + 2]};
+    const int32_t e1 = off[I + 1];
+    for (int32_t e = off[I] + lane; e < e1; e += 64) {
         const int32_t J = col[e];
-        const double w = kern_pts<R>(nX + 3 * I, nX + 3 * J, expo);
+        const double w = frac_kernel<R>(xi, nX + 3 * J, expo);
         acc[0] += w * na[J];
-        for (int c = 0; c < k; ++c) acc[1 + c] += w * nm[(int64_t)J * k + c];
+#pragma unroll
+        for (int c = 0; c < kMaxGroupCols; ++c)
+            if (c < k) acc[1 + c] += w * nm[(int64_t)J * k + c];
     }
-    for (int c = 0; c <= k; ++c) yt[I * (k + 1) + c] = acc[c];
+#pragma unroll
+    for (int c = 0; c <= kMaxGroupCols; ++c) {
+        if (c > k) break;
+        double v = acc[c];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        acc[c] = v;
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int c = 0; c <= kMaxGroupCols; ++c)
+            if (c <= k) yt[I * (k + 1) + c] = acc[c];
+    }
+}
+
+// Inadmissible (exact) blocks for leaves of at most 8 faces: one wave per row leaf L, lane
+// (i, j) = (lane / 8, lane % 8) takes the pair (face i of L, face j of J) for every leaf J of
+// L's list, all lanes walking the same list; the 8 lanes of face i are then added in a fixed
+// order and lane (i, 0) adds the far field of L's path to the root (downward pass).
+template <class R, class UB>
+__global__ __launch_bounds__(256) void k_bct_leaf8(int64_t nF, int leaf, int64_t P, const int32_t* __restrict__ order,
+                                                   const double4* __restrict__ dx, const UB* __restrict__ ub, int kp,
+                                                   int k, const int32_t* __restrict__ noff,
+                                                   const int32_t* __restrict__ ncol, const double* __restrict__ yt,
+                                                   double expo, double* __restrict__ z, int64_t zstride)
+{
+    const int64_t L = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
+    const int64_t nleaf = (nF + leaf - 1) / leaf;
+    if (L >= nleaf) return;                   // the whole wave
+    const int i = lane >> 3, j = lane & 7;
+    const int64_t ps = L * leaf + i;
+    const bool own = i < leaf && ps < nF;
+    const int32_t s = own ? order[ps] : -1;
+    double xs[3] = {0.0, 0.0, 0.0}, us[kMaxGroupCols], acc[kMaxGroupCols];
+    if (own) {
+        const double4 X = dx[s];
+        xs[0] = X.x; xs[1] = X.y; xs[2] = X.z;
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxGroupCols; ++c) {
+        us[c] = (own && c < k) ? (double)ub[(int64_t)s * kp + c] : 0.0;
+        acc[c] = 0.0;
+    }
+    const int32_t e1 = noff[L + 1];
+    for (int32_t e = noff[L]; e < e1; ++e) {
+        const int64_t pt = (int64_t)ncol[e] * leaf + j;
+        if (!own || j >= leaf || pt >= nF) continue;
+        const int32_t t = order[pt];
+        if (t == s) continue;
+        const double4 Y = dx[t];
+        const double y[3] = {Y.x, Y.y, Y.z};
+        const double w = frac_kernel<R>(xs, y, expo) * Y.w;
+#pragma unroll
+        for (int c = 0; c < kMaxGroupCols; ++c)
+            if (c < k) acc[c] += w * (us[c] - (double)ub[(int64_t)t * kp + c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxGroupCols; ++c) {
+        if (c >= k) break;
+        double v = acc[c];
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 1, 64);
+        acc[c] = v;
+    }
+    if (!own || j != 0) return;
+    double y0 = 0.0, yc[kMaxGroupCols];
+#pragma unroll
+    for (int c = 0; c < kMaxGroupCols; ++c) yc[c] = 0.0;
+    for (int64_t node = P + L; node >= 1; node >>= 1) {
+        y0 += yt[node * (k + 1)];
+#pragma unroll
+        for (int c = 0; c < kMaxGroupCols; ++c)
+            if (c < k) yc[c] += yt[node * (k + 1) + 1 + c];
+    }
+#pragma unroll
+    for (int c = 0; c < kMaxGroupCols; ++c)
+        if (c < k) z[c * zstride + s] = acc[c] + (us[c] * y0 - yc[c]);
 }
 
 template <class R, class UB>
@@ -572,6 +648,7 @@ __global__ __launch_bounds__(256) void k_bct_faces(int64_t nF, int leaf, int64_t
     const double4 X = dx[s];
     const double xs[3] = {X.x, X.y, X.z};
     double us[kMaxGroupCols], acc[kMaxGroupCols];
+#pragma unroll
     for (int c = 0; c < kMaxGroupCols; ++c) {
         us[c] = c < k ? (double)ub[(int64_t)s * kp + c] : 0.0;
         acc[c] = 0.0;
@@ -587,17 +664,24 @@ __global__ __launch_bounds__(256) void k_bct_faces(int64_t nF, int leaf, int64_t
             const double4 Y = dx[t];
             const double y[3] = {Y.x, Y.y, Y.z};
             const double w = frac_kernel<R>(xs, y, expo) * Y.w;
-            for (int c = 0; c < k; ++c) acc[c] += w * (us[c] - (double)ub[(int64_t)t * kp + c]);
+#pragma unroll
+            for (int c = 0; c < kMaxGroupCols; ++c)
+                if (c < k) acc[c] += w * (us[c] - (double)ub[(int64_t)t * kp + c]);
         }
     }
     // far field: the leaf's and its ancestors' y~, root last
     double y0 = 0.0, yc[kMaxGroupCols];
+#pragma unroll
     for (int c = 0; c < kMaxGroupCols; ++c) yc[c] = 0.0;
     for (int64_t node = P + L; node >= 1; node >>= 1) {
         y0 += yt[node * (k + 1)];
-        for (int c = 0; c < k; ++c) yc[c] += yt[node * (k + 1) + 1 + c];
+#pragma unroll
+        for (int c = 0; c < kMaxGroupCols; ++c)
+            if (c < k) yc[c] += yt[node * (k + 1) + 1 + c];
     }
-    for (int c = 0; c < k; ++c) z[c * zstride + s] = acc[c] + (us[c] * y0 - yc[c]);
+#pragma unroll
+    for (int c = 0; c < kMaxGroupCols; ++c)
+        if (c < k) z[c * zstride + s] = acc[c] + (us[c] * y0 - yc[c]);
 }
 
 template <class UB>
@@ -610,15 +694,26 @@ hipError_t bct_launch(const BhBuffers& b, const BctLists& bl, int64_t nF, int le
     hipLaunchKernelGGL(k_bh_moment_leaves<UB>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, nF, leaf, P,
                        b.order, fd.dx, ub, kp, k, nm);
     hipLaunchKernelGGL(k_bh_moment_levels, dim3(1), dim3(1024), 0, s, P, k, nm);
-    const dim3 gm((unsigned)((M + 255) / 256)), gf((unsigned)((nF + 255) / 256)), blk(256);
+    // one wave (64 lanes) per node for the admissible blocks, per leaf for the exact ones
+    const int64_t nleaf = (nF + leaf - 1) / leaf;
+    const dim3 gm((unsigned)((M * 64 + 255) / 256)), gl((unsigned)((nleaf * 64 + 255) / 256)),
+        gf((unsigned)((nF + 255) / 256)), blk(256);
     if (f64) {
         hipLaunchKernelGGL(k_bct_far<double>, gm, blk, 0, s, M, k, bl.far_off, bl.far_col, b.nX, b.na, nm, expo, yt);
-        hipLaunchKernelGGL((k_bct_faces<double, UB>), gf, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
-                           bl.near_off, bl.near_col, yt, expo, z, zstride);
+        if (leaf <= 8)
+            hipLaunchKernelGGL((k_bct_leaf8<double, UB>), gl, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
+                               bl.near_off, bl.near_col, yt, expo, z, zstride);
+        else
+            hipLaunchKernelGGL((k_bct_faces<double, UB>), gf, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
+                               bl.near_off, bl.near_col, yt, expo, z, zstride);
     } else {
         hipLaunchKernelGGL(k_bct_far<float>, gm, blk, 0, s, M, k, bl.far_off, bl.far_col, b.nX, b.na, nm, expo, yt);
-        hipLaunchKernelGGL((k_bct_faces<float, UB>), gf, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
-                           bl.near_off, bl.near_col, yt, expo, z, zstride);
+        if (leaf <= 8)
+            hipLaunchKernelGGL((k_bct_leaf8<float, UB>), gl, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
+                               bl.near_off, bl.near_col, yt, expo, z, zstride);
+        else
+            hipLaunchKernelGGL((k_bct_faces<float, UB>), gf, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
+                               bl.near_off, bl.near_col, yt, expo, z, zstride);
     }
     return hipGetLastError();
 }

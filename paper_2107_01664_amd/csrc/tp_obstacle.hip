@@ -4,6 +4,7 @@
 //   w = a_O(S) r2^(-p/2),  phi(T) += w,  dphi/dX_T += -p w d / r2.
 // Sums run over the obstacle in a fixed order, so results are reproducible.
 #include "tp_obstacle.h"
+#include "tp_tree.h"
 
 namespace tp {
 
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_obs_pairs(const double4* __restrict_
 }
 
 // Barnes-Hut form (params.theta > 0): the tree of launch_bh_build over the obstacle's faces,
-// one thread per surface face, walked depth first (left child first) without a stack.  The
+// one thread per surface face, the lanes of a wave walking it together (wave_walk).  The
 // potential is evaluated at the barycenter X_T, a point, so node I is admissible when
 // r_I^2 < theta^2 dist(X_T, box_I)^2 (decided in FP64 without fused multiply-adds, so the
 // interaction lists are a function of the meshes alone) and then contributes
@@ -112,8 +113,8 @@ template <bool P6>
 __global__ __launch_bounds__(256) void k_obs_bh(ObsTreeArgs A)
 {
     const int64_t T = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (T >= A.nF) return;
-    const double4 x = A.dx[T];
+    const bool live = T < A.nF;                 // every lane walks with its wave
+    const double4 x = A.dx[live ? T : 0];
     double phi = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
     unsigned long long nfar = 0, nnear = 0;
     auto visit = [&](double yx, double yy, double yz, double w) {
@@ -127,33 +128,22 @@ __global__ __launch_bounds__(256) void k_obs_bh(ObsTreeArgs A)
         g1 += c * d1;
         g2 += c * d2;
     };
-    int64_t node = 1;
-    for (;;) {
-        bool down = false;
-        if (A.na[node] > 0.0) {
-            if (point_admissible(A, x, node)) {
-                visit(A.nX[3 * node], A.nX[3 * node + 1], A.nX[3 * node + 2], A.na[node]);
-                ++nfar;
-            } else if (node >= A.P) {
-                const int64_t l = node - A.P;
-                const int64_t q1 = min((l + 1) * (int64_t)A.leaf, A.nFo);
-                for (int64_t q = l * A.leaf; q < q1; ++q) {
-                    const double4 o = A.xo[A.order[q]];
-                    visit(o.x, o.y, o.z, o.w);
-                    ++nnear;
-                }
-            } else {
-                down = true;
+    wave_walk(
+        A.na, A.P, live, [&](int node) { return point_admissible(A, x, node); },
+        [&](int node) {
+            visit(A.nX[3 * node], A.nX[3 * node + 1], A.nX[3 * node + 2], A.na[node]);
+            ++nfar;
+        },
+        [&](int node) {
+            const int64_t l = node - A.P;
+            const int64_t q1 = min((l + 1) * (int64_t)A.leaf, A.nFo);
+            for (int64_t q = l * A.leaf; q < q1; ++q) {
+                const double4 o = A.xo[A.order[q]];
+                visit(o.x, o.y, o.z, o.w);
+                ++nnear;
             }
-        }
-        if (down) {
-            node = 2 * node;
-            continue;
-        }
-        while (node & 1) node >>= 1;      // climb out of right children (and the root)
-        if (node == 0) break;
-        node += 1;                        // right sibling
-    }
+        });
+    if (!live) return;
     const int64_t gs = A.gs;
     A.e[T] = x.w * phi;
     A.g[T] = x.w * g0;

@@ -1,0 +1,52 @@
+// Walk of the heap-ordered Barnes-Hut tree by a whole wave (64 lanes) at once.
+//
+// Each lane has its own interaction list (its own admissibility tests), but the lanes of a
+// wave hold neighbouring faces in Morton order, so their lists overlap.  The wave visits a
+// node when at least one of its lanes needs it, in the order of a single depth-first walk
+// (left child first), so every lane meets the terms of its own list in the order it would
+// walking alone, and all lanes read the same node at the same time.  A lane that takes a
+// node -- far(node) when the node is admissible for it, near(node) for a leaf that is not --
+// skips the node's subtree while the wave walks it for other lanes.  Lanes without a face
+// (live = false) take no node.  All lanes of the wave must call this together.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace tp {
+
+template <class Adm, class Far, class Near>
+__device__ __forceinline__ void wave_walk(const double* __restrict__ na, int64_t P, bool live, Adm&& adm, Far&& far,
+                                          Near&& near)
+{
+    int node = 1;
+    int skip = live ? 0 : 1;   // root of the subtree this lane skips (0: none; 1: the whole tree)
+    for (;;) {
+        node = __builtin_amdgcn_readfirstlane(node);   // the same on every lane
+        if (skip) {
+            const int dn = 31 - __builtin_clz((unsigned)node), ds = 31 - __builtin_clz((unsigned)skip);
+            if (dn < ds || (node >> (dn - ds)) != skip) skip = 0;   // left the skipped subtree
+        }
+        bool down = false;
+        if (!skip && na[node] > 0.0) {
+            if (adm(node)) {
+                far(node);
+                skip = node;
+            } else if (node >= P) {
+                near(node);
+                skip = node;
+            } else {
+                down = true;
+            }
+        }
+        if (__ballot(down) != 0ull) {
+            node = 2 * node;
+            continue;
+        }
+        while (node & 1) node >>= 1;   // climb out of right children (and the root)
+        if (node == 0) break;
+        node += 1;                     // right sibling
+    }
+}
+
+}  // namespace tp
