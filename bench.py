@@ -327,7 +327,7 @@ def sweep():
     amplitude 0.05) in every variant against the FP64 direct sums on the GPU (which the GPU
     tests hold to the oracle at sampled vertices of the same mesh), and direct vs
     Barnes-Hut on the linked tori (51,200 faces).  Times are wall time of one synchronous
-    E + dE call (best of 3)."""
+    E + dE call and of one E call (best of 3 each)."""
     import numpy as np
     import torch
     from paper_2107_01664_amd import meshgen as mg
@@ -357,16 +357,19 @@ def sweep():
                 (E, g), ms = _timed(lambda: P.gradient())
                 g = g.cpu().numpy()
                 terms = P.bh_stats() if kw.get("theta") else None
+                _, ms_e = _timed(lambda: P.energy())
             if ref is None:
                 ref = (E, g)
-                rows[name] = {"E": E, "ms": ms}
+                rows[name] = {"E": E, "ms": ms, "energy_only_ms": ms_e}
                 print(f"[sweep] {wname} {name}: {ms:.1f} ms", file=sys.stderr, flush=True)
                 continue
-            r = {"E": E, "ms": ms, "E_rel_err": abs(E - ref[0]) / ref[0], "dE_rel_err": rel(g, ref[1])}
+            r = {"E": E, "ms": ms, "energy_only_ms": ms_e, "E_rel_err": abs(E - ref[0]) / ref[0],
+                 "dE_rel_err": rel(g, ref[1])}
             if terms:
                 r["terms_far_near"] = list(terms)
             rows[name] = r
-            print(f"[sweep] {wname} {name}: {ms:.1f} ms, E {r['E_rel_err']:.2e}, dE {r['dE_rel_err']:.2e}",
+            print(f"[sweep] {wname} {name}: {ms:.1f} ms (E alone {ms_e:.1f} ms), E {r['E_rel_err']:.2e}, "
+                  f"dE {r['dE_rel_err']:.2e}",
                   file=sys.stderr, flush=True)
         report[wname] = {"faces": m.nF, "pairs": float(m.nF) * (m.nF - 1), "variants": rows}
         # the fractional operator L^sigma u (3 random columns): direct sums, Barnes-Hut on the

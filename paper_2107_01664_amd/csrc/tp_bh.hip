@@ -23,9 +23,10 @@
 // a_S a_I, a leaf that is not admissible adds the exact terms of its faces T != S, other
 // nodes are opened.  The
 // differential is that of E_BH with the lists held fixed: the face S side is summed per
-// thread; the target side (dX, da of a face T or a node I) is added with device-scope
-// atomics; node derivatives then reach their member faces through X_I = sum a_T X_T / a_I
-// and a_I = sum a_T, walking up each face's ancestors.  The atomic sums make the last bits
+// thread; the target side (dX, da of a face T or a node I) is summed across the wave and
+// added with device-scope atomics, one set per wave and target; node derivatives then
+// reach their member faces through X_I = sum a_T X_T / a_I and a_I = sum a_T, walking up
+// each face's ancestors.  The atomic sums make the last bits
 // of dE depend on scheduling; E itself is summed per face in a fixed order.
 #include "tp_internal.h"
 #include "tp_tree.h"
@@ -307,7 +308,8 @@ __global__ __launch_bounds__(256) void k_bh_traverse(BhArgs A)
     double gX[3] = {0, 0, 0}, gN[3] = {0, 0, 0}, ga = 0.0, e = 0.0;
     unsigned long long nfar = 0, nnear = 0;
 
-    auto visit = [&](const double* y, double w, double* acc, int64_t stride) {
+    // one term of this lane with target (y, w): face-side sums here, target-side parts in tg
+    auto visit = [&](const double* y, double w, double (&tg)[4]) {
         R K, dKdd[3], dKdN[3];
         term<R, GEN>(xs, ns, y, A, K, dKdd, dKdN);
         const double Kd = (double)K;
@@ -318,29 +320,46 @@ __global__ __launch_bounds__(256) void k_bh_traverse(BhArgs A)
                 const double gd = f * (double)dKdd[m];
                 gX[m] += gd;
                 gN[m] += f * (double)dKdN[m];
-                unsafeAtomicAdd(acc + m * stride, -gd);
+                tg[m] = -gd;
             }
             ga += w * Kd;
-            unsafeAtomicAdd(acc + 3 * stride, aS * Kd);
+            tg[3] = aS * Kd;
+        }
+    };
+    // the target-side parts of the wave's lanes are summed across the wave first, so each
+    // target receives one set of atomic additions per wave
+    auto push = [&](const double (&tg)[4], double* acc, int64_t stride) {
+        for (int m = 0; m < 4; ++m) {
+            const double v = wave_sum(tg[m]);
+            if ((threadIdx.x & 63) == 0) unsafeAtomicAdd(acc + m * stride, v);
         }
     };
 
-    wave_walk(
+    wave_walk_act(
         A.na, A.P, live, [&](int node) { return admissible(A, slo, shi, sr2, node); },
-        [&](int node) {
-            visit(A.nX + 3 * (int64_t)node, A.na[node], A.accN + node, 2 * A.P);
-            ++nfar;
-        },
-        [&](int node) {
-            const int64_t l = node - A.P;
-            const int64_t p1 = min((l + 1) * (int64_t)A.leaf, A.nF);
-            for (int64_t q = l * A.leaf; q < p1; ++q) {
-                const int32_t t = A.order[q];
-                if (t == s) continue;
-                const double4 Y = A.dx[t];
-                const double y[3] = {Y.x, Y.y, Y.z};
-                visit(y, Y.w, A.accF + t, A.nF);
-                ++nnear;
+        [&](int node, int took) {
+            if (__ballot(took == 1) != 0ull) {
+                double tg[4] = {0.0, 0.0, 0.0, 0.0};
+                if (took == 1) {
+                    visit(A.nX + 3 * (int64_t)node, A.na[node], tg);
+                    ++nfar;
+                }
+                if (GRAD) push(tg, A.accN + node, 2 * A.P);
+            }
+            if (__ballot(took == 2) != 0ull) {
+                const int64_t l = node - A.P;
+                const int64_t p1 = min((l + 1) * (int64_t)A.leaf, A.nF);
+                for (int64_t q = l * A.leaf; q < p1; ++q) {
+                    const int32_t t = A.order[q];
+                    double tg[4] = {0.0, 0.0, 0.0, 0.0};
+                    if (took == 2 && t != s) {
+                        const double4 Y = A.dx[t];
+                        const double y[3] = {Y.x, Y.y, Y.z};
+                        visit(y, Y.w, tg);
+                        ++nnear;
+                    }
+                    if (GRAD) push(tg, A.accF + t, A.nF);
+                }
             }
         });
     if (!live) return;
@@ -598,18 +617,33 @@ __global__ __launch_bounds__(256) void k_bct_leaf8(int64_t nF, int leaf, int64_t
         us[c] = (own && c < k) ? (double)ub[(int64_t)s * kp + c] : 0.0;
         acc[c] = 0.0;
     }
-    const int32_t e1 = noff[L + 1];
-    for (int32_t e = noff[L]; e < e1; ++e) {
-        const int64_t pt = (int64_t)ncol[e] * leaf + j;
-        if (!own || j >= leaf || pt >= nF) continue;
-        const int32_t t = order[pt];
-        if (t == s) continue;
-        const double4 Y = dx[t];
-        const double y[3] = {Y.x, Y.y, Y.z};
-        const double w = frac_kernel<R>(xs, y, expo) * Y.w;
+    // the list in groups of U leaves: the U gathers of a group are issued before any of them
+    // is used, which keeps U memory round trips in flight per lane
+    constexpr int U = 4;
+    const bool lane_on = own && j < leaf;
+    const int32_t e0 = noff[L], e1 = noff[L + 1];
+    for (int32_t e = e0; e < e1; e += U) {
+        int32_t t[U];
 #pragma unroll
-        for (int c = 0; c < kMaxGroupCols; ++c)
-            if (c < k) acc[c] += w * (us[c] - (double)ub[(int64_t)t * kp + c]);
+        for (int q = 0; q < U; ++q) {
+            t[q] = -1;
+            if (lane_on && e + q < e1) {
+                const int64_t pt = (int64_t)ncol[e + q] * leaf + j;
+                if (pt < nF) t[q] = order[pt];
+            }
+        }
+        double4 Y[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) Y[q] = t[q] >= 0 ? dx[t[q]] : make_double4(0.0, 0.0, 0.0, 0.0);
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+            if (t[q] < 0 || t[q] == s) continue;
+            const double y[3] = {Y[q].x, Y[q].y, Y[q].z};
+            const double w = frac_kernel<R>(xs, y, expo) * Y[q].w;
+#pragma unroll
+            for (int c = 0; c < kMaxGroupCols; ++c)
+                if (c < k) acc[c] += w * (us[c] - (double)ub[(int64_t)t[q] * kp + c]);
+        }
     }
 #pragma unroll
     for (int c = 0; c < kMaxGroupCols; ++c) {

@@ -15,9 +15,13 @@
 
 namespace tp {
 
-template <class Adm, class Far, class Near>
-__device__ __forceinline__ void wave_walk(const double* __restrict__ na, int64_t P, bool live, Adm&& adm, Far&& far,
-                                          Near&& near)
+// The walk itself: act(node, took) is called on every lane at every node the wave visits,
+// with took = 1 when the node is admissible for the lane, 2 when it is a leaf the lane sums
+// exactly, 0 otherwise (the call is uniform across the wave, so act may use cross-lane
+// operations).
+template <class Adm, class Act>
+__device__ __forceinline__ void wave_walk_act(const double* __restrict__ na, int64_t P, bool live, Adm&& adm,
+                                              Act&& act)
 {
     int node = 1;
     int skip = live ? 0 : 1;   // root of the subtree this lane skips (0: none; 1: the whole tree)
@@ -28,17 +32,19 @@ __device__ __forceinline__ void wave_walk(const double* __restrict__ na, int64_t
             if (dn < ds || (node >> (dn - ds)) != skip) skip = 0;   // left the skipped subtree
         }
         bool down = false;
+        int took = 0;
         if (!skip && na[node] > 0.0) {
             if (adm(node)) {
-                far(node);
+                took = 1;
                 skip = node;
             } else if (node >= P) {
-                near(node);
+                took = 2;
                 skip = node;
             } else {
                 down = true;
             }
         }
+        act(node, took);
         if (__ballot(down) != 0ull) {
             node = 2 * node;
             continue;
@@ -47,6 +53,23 @@ __device__ __forceinline__ void wave_walk(const double* __restrict__ na, int64_t
         if (node == 0) break;
         node += 1;                     // right sibling
     }
+}
+
+template <class Adm, class Far, class Near>
+__device__ __forceinline__ void wave_walk(const double* __restrict__ na, int64_t P, bool live, Adm&& adm, Far&& far,
+                                          Near&& near)
+{
+    wave_walk_act(na, P, live, adm, [&](int node, int took) {
+        if (took == 1) far(node);
+        else if (took == 2) near(node);
+    });
+}
+
+// Sum of v over the 64 lanes of a wave, in a fixed order (every lane gets the sum).
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
 }  // namespace tp
