@@ -375,7 +375,7 @@ struct tp_problem {
     DevBuf<double> R, Y, W1, W2, gbuf, dir, Vt, Vsave;
 
     // Barnes-Hut tree and work arrays (params.theta > 0)
-    DevBuf<double> bh_nm;   // node moments of the Barnes-Hut fractional apply [2P][k]
+    DevBuf<double> bh_nm;   // node moments of the Barnes-Hut fractional apply [2P][kp]
     // block cluster tree (chi > 0): device CSR lists, far-field values [2P][k + 1], the
     // geometry version they describe and their block counts
     DevBuf<int32_t> bct_far_off, bct_far_col, bct_near_off, bct_near_col;
@@ -940,7 +940,7 @@ tp_status ensure_bh(tp_problem* P)
     TP_TRY(P->bh_accF.ensure(4 * nF, s));
     TP_TRY(P->bh_accN.ensure(4 * M, s));
     TP_TRY(P->bh_counts.ensure(2, s));
-    TP_TRY(P->bh_nm.ensure((size_t)M * kMaxGroupCols, s));
+    TP_TRY(P->bh_nm.ensure((size_t)M * ((kMaxGroupCols + 3) / 4 * 4), s));
     BhBuffers& b = P->bh;
     b.flo = P->bh_flo.p; b.fhi = P->bh_fhi.p; b.fr2 = P->bh_fr2.p; b.box = P->bh_box.p;
     b.keys_in = P->bh_kin.p; b.keys_out = P->bh_kout.p; b.sort_tmp = P->bh_tmp.p; b.sort_bytes = tb;
@@ -1029,7 +1029,7 @@ tp_status ensure_bct(tp_problem* P)
     TP_TRY(P->bct_far_col.ensure(fcol.size(), s));
     TP_TRY(P->bct_near_off.ensure(noff.size(), s));
     TP_TRY(P->bct_near_col.ensure(ncol.size(), s));
-    TP_TRY(P->bct_yt.ensure((size_t)M * (kMaxGroupCols + 1), s));
+    TP_TRY(P->bct_yt.ensure((size_t)M * ((kMaxGroupCols + 3) / 4 * 4 + 4), s));
     TP_HIP(hipMemcpyAsync(P->bct_far_off.p, foff.data(), sizeof(int32_t) * foff.size(), hipMemcpyHostToDevice, s));
     TP_HIP(hipMemcpyAsync(P->bct_far_col.p, fcol.data(), sizeof(int32_t) * fcol.size(), hipMemcpyHostToDevice, s));
     TP_HIP(hipMemcpyAsync(P->bct_near_off.p, noff.data(), sizeof(int32_t) * noff.size(), hipMemcpyHostToDevice, s));
@@ -1246,7 +1246,7 @@ tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, in
             if (P->prm.chi > 0.0) {
                 // block cluster tree: hierarchical product, the row sums straight into zbuf
                 TP_TRY(ensure_bct(P));
-                TP_TRY(P->bh_nm.ensure((size_t)bh_node_count(P->nF, P->prm.leaf_size, nullptr) * kc, s));
+                TP_TRY(P->bh_nm.ensure((size_t)bh_node_count(P->nF, P->prm.leaf_size, nullptr) * kp, s));
                 BctLists bl;
                 bl.far_off = P->bct_far_off.p; bl.far_col = P->bct_far_col.p;
                 bl.near_off = P->bct_near_off.p; bl.near_col = P->bct_near_col.p;
@@ -1257,7 +1257,7 @@ tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, in
             if (P->prm.theta > 0.0) {
                 // Barnes-Hut on the kernel matrix: the row sums straight into zbuf
                 TP_TRY(ensure_tree(P));
-                TP_TRY(P->bh_nm.ensure((size_t)bh_node_count(P->nF, P->prm.leaf_size, nullptr) * kc, s));
+                TP_TRY(P->bh_nm.ensure((size_t)bh_node_count(P->nF, P->prm.leaf_size, nullptr) * kp, s));
                 TP_HIP(launch_bh_frac(P->bh, P->nF, P->prm.leaf_size, P->prm.theta, prec, P->sigma, P->fd, P->ub.p, kp,
                                       kc, P->bh_nm.p, P->zbuf.p, pl.irows, s));
                 continue;

@@ -417,32 +417,60 @@ __global__ void k_bh_assemble(int64_t nF, int leaf, int64_t P, const int32_t* __
 // k = |d|^-(2 sigma + 2).  Only the face S side is summed, so there are no atomics and
 // the result is deterministic.  z(S) (without the factor a_S) goes to z[c * zstride + S],
 // the layout of the direct kernel's reduced sums.
+//
+// Rows of face averages (ub), node moments (nm) and far-field values are KP wide, KP = the
+// column count rounded up to 4 (the padding holds zeros), and are read as 4-wide vectors,
+// so a row costs one memory round trip; the kernels are instantiated for KP = 4, 8, 12.
 
-// Node moments, leaves first (member faces in sorted order), then level by level.
-template <class UB>
+template <class UB> struct Vec4Of;
+template <> struct Vec4Of<float> { using type = float4; };
+template <> struct Vec4Of<double> { using type = double4; };
+
+// out[0 .. KP) = row[0 .. KP) (16- or 32-byte aligned)
+template <int KP, class T>
+__device__ __forceinline__ void load_row(const T* __restrict__ row, double (&out)[KP])
+{
+    using V = typename Vec4Of<T>::type;
+#pragma unroll
+    for (int h = 0; h < KP / 4; ++h) {
+        const V v = reinterpret_cast<const V*>(row)[h];
+        out[4 * h] = (double)v.x;
+        out[4 * h + 1] = (double)v.y;
+        out[4 * h + 2] = (double)v.z;
+        out[4 * h + 3] = (double)v.w;
+    }
+}
+
+// Node moments [2P][KP], leaves first (member faces in sorted order), then level by level.
+template <class UB, int KP>
 __global__ void k_bh_moment_leaves(int64_t nF, int leaf, int64_t P, const int32_t* __restrict__ order,
-                                   const double4* __restrict__ dx, const UB* __restrict__ ub, int kp, int k,
+                                   const double4* __restrict__ dx, const UB* __restrict__ ub,
                                    double* __restrict__ nm)
 {
     const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (l >= P) return;
-    double acc[kMaxGroupCols];
-    for (int c = 0; c < kMaxGroupCols; ++c) acc[c] = 0.0;
+    double acc[KP];
+#pragma unroll
+    for (int c = 0; c < KP; ++c) acc[c] = 0.0;
     for (int64_t p = l * leaf; p < (l + 1) * leaf && p < nF; ++p) {
         const int32_t t = order[p];
         const double a = dx[t].w;
-        for (int c = 0; c < k; ++c) acc[c] = acc[c] + a * (double)ub[(int64_t)t * kp + c];
+        double u[KP];
+        load_row<KP>(ub + (int64_t)t * KP, u);
+#pragma unroll
+        for (int c = 0; c < KP; ++c) acc[c] = acc[c] + a * u[c];
     }
-    for (int c = 0; c < k; ++c) nm[(P + l) * k + c] = acc[c];
+#pragma unroll
+    for (int c = 0; c < KP; ++c) nm[(P + l) * KP + c] = acc[c];
 }
 
-__global__ __launch_bounds__(1024) void k_bh_moment_levels(int64_t P, int k, double* __restrict__ nm)
+__global__ __launch_bounds__(1024) void k_bh_moment_levels(int64_t P, int kp, double* __restrict__ nm)
 {
     for (int64_t n0 = P / 2; n0 >= 1; n0 /= 2) {
-        for (int64_t e = threadIdx.x; e < n0 * k; e += blockDim.x) {
-            const int64_t node = n0 + e / k;
-            const int c = (int)(e % k);
-            nm[node * k + c] = nm[2 * node * k + c] + nm[(2 * node + 1) * k + c];
+        for (int64_t e = threadIdx.x; e < n0 * kp; e += blockDim.x) {
+            const int64_t node = n0 + e / kp;
+            const int c = (int)(e % kp);
+            nm[node * kp + c] = nm[2 * node * kp + c] + nm[(2 * node + 1) * kp + c];
         }
         __syncthreads();
     }
@@ -459,8 +487,8 @@ __device__ __forceinline__ double frac_kernel(const double (&xs)[3], const doubl
     return pow((double)r2, expo);
 }
 
-template <class R, class UB>
-__global__ __launch_bounds__(256) void k_bh_frac(BhArgs A, const UB* __restrict__ ub, int kp, int k,
+template <class R, class UB, int KP>
+__global__ __launch_bounds__(256) void k_bh_frac(BhArgs A, const UB* __restrict__ ub, int k,
                                                  const double* __restrict__ nm, double expo,
                                                  double* __restrict__ z, int64_t zstride)
 {
@@ -475,20 +503,19 @@ __global__ __launch_bounds__(256) void k_bh_frac(BhArgs A, const UB* __restrict_
         shi[m] = A.fhi[3 * s + m];
     }
     const double sr2 = A.fr2[s];
-    double us[kMaxGroupCols], acc[kMaxGroupCols];
+    double us[KP], acc[KP];
+    load_row<KP>(ub + (int64_t)s * KP, us);
 #pragma unroll
-    for (int c = 0; c < kMaxGroupCols; ++c) {
-        us[c] = c < k ? (double)ub[(int64_t)s * kp + c] : 0.0;
-        acc[c] = 0.0;
-    }
+    for (int c = 0; c < KP; ++c) acc[c] = 0.0;
     wave_walk(
         A.na, A.P, live, [&](int node) { return admissible(A, slo, shi, sr2, node); },
         [&](int node) {
+            double m[KP];
+            load_row<KP>(nm + (int64_t)node * KP, m);
             const double w = frac_kernel<R>(xs, A.nX + 3 * (int64_t)node, expo);
             const double a = A.na[node];
 #pragma unroll
-            for (int c = 0; c < kMaxGroupCols; ++c)
-                if (c < k) acc[c] += w * (a * us[c] - nm[(int64_t)node * k + c]);
+            for (int c = 0; c < KP; ++c) acc[c] += w * (a * us[c] - m[c]);
         },
         [&](int node) {
             const int64_t l = node - A.P;
@@ -497,37 +524,45 @@ __global__ __launch_bounds__(256) void k_bh_frac(BhArgs A, const UB* __restrict_
                 const int32_t t = A.order[q];
                 if (t == s) continue;
                 const double4 Y = A.dx[t];
+                double ut[KP];
+                load_row<KP>(ub + (int64_t)t * KP, ut);
                 const double y[3] = {Y.x, Y.y, Y.z};
                 const double w = frac_kernel<R>(xs, y, expo) * Y.w;
 #pragma unroll
-                for (int c = 0; c < kMaxGroupCols; ++c)
-                    if (c < k) acc[c] += w * (us[c] - (double)ub[(int64_t)t * kp + c]);
+                for (int c = 0; c < KP; ++c) acc[c] += w * (us[c] - ut[c]);
             }
         });
     if (!live) return;
 #pragma unroll
-    for (int c = 0; c < kMaxGroupCols; ++c)
+    for (int c = 0; c < KP; ++c)
         if (c < k) z[c * zstride + s] = acc[c];
 }
 
-template <class UB>
+template <class UB, int KP>
+void moments_launch(const BhBuffers& b, int64_t nF, int leaf, int64_t P, const FaceData& fd, const UB* ub,
+                    double* nm, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_bh_moment_leaves<UB, KP>), dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, nF, leaf,
+                       P, b.order, fd.dx, ub, nm);
+    hipLaunchKernelGGL(k_bh_moment_levels, dim3(1), dim3(1024), 0, s, P, KP, nm);
+}
+
+template <class UB, int KP>
 hipError_t bh_frac_launch(const BhBuffers& b, int64_t nF, int leaf, double theta, bool f64, const FaceData& fd,
-                          const UB* ub, int kp, int k, double expo, double* nm, double* z, int64_t zstride,
-                          hipStream_t s)
+                          const UB* ub, int k, double expo, double* nm, double* z, int64_t zstride, hipStream_t s)
 {
     int64_t P = 0;
     (void)bh_node_count(nF, leaf, &P);
-    hipLaunchKernelGGL(k_bh_moment_leaves<UB>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, nF, leaf, P,
-                       b.order, fd.dx, ub, kp, k, nm);
-    hipLaunchKernelGGL(k_bh_moment_levels, dim3(1), dim3(1024), 0, s, P, k, nm);
+    moments_launch<UB, KP>(b, nF, leaf, P, fd, ub, nm, s);
     BhArgs A;
     A.nF = nF; A.P = P; A.leaf = leaf; A.theta2 = theta * theta; A.alpha = 0.0; A.beta = 0.0;
     A.order = b.order; A.dx = fd.dx; A.dn = fd.dn; A.flo = b.flo; A.fhi = b.fhi; A.fr2 = b.fr2;
     A.na = b.na; A.nX = b.nX; A.nlo = b.nlo; A.nhi = b.nhi; A.nr2 = b.nr2;
     A.gS = nullptr; A.eS = nullptr; A.accF = nullptr; A.accN = nullptr; A.counts = nullptr;
+    // pair terms in the precision of the face averages (FP64 for TP_PREC_FP64, else FP32)
+    (void)f64;
     const dim3 grid((unsigned)((nF + 255) / 256)), block(256);
-    if (f64) hipLaunchKernelGGL((k_bh_frac<double, UB>), grid, block, 0, s, A, ub, kp, k, nm, expo, z, zstride);
-    else hipLaunchKernelGGL((k_bh_frac<float, UB>), grid, block, 0, s, A, ub, kp, k, nm, expo, z, zstride);
+    hipLaunchKernelGGL((k_bh_frac<UB, UB, KP>), grid, block, 0, s, A, ub, k, nm, expo, z, zstride);
     return hipGetLastError();
 }
 
@@ -541,19 +576,13 @@ hipError_t bh_frac_launch(const BhBuffers& b, int64_t nF, int leaf, double theta
 // then adds the y~ of its leaf and all its ancestors (the downward pass, summed along the
 // face's path) and the exact terms of the leaves inadmissible for its own:
 //   z(S) = ubar_S Y0(S) - Y(S) + sum_{T in near leaves, T != S} k(X_S, X_T) a_T (ubar_S - ubar_T).
-
-template <class R>
-__device__ __forceinline__ double kern_pts(const double* x, const double* y, double expo)
-{
-    const double xs[3] = {x[0], x[1], x[2]};
-    return frac_kernel<R>(xs, y, expo);
-}
+// y~ rows are 4 + KP wide: [sum w a_J, 0, 0, 0, sum w m_J (KP)].
 
 // Admissible blocks: one wave per row node I.  The lanes take the node's list in strides of
-// 64 entries; the k + 1 sums are then added across the wave in a fixed order (butterfly), so
-// the result does not depend on timing.
-template <class R>
-__global__ __launch_bounds__(256) void k_bct_far(int64_t M, int k, const int32_t* __restrict__ off,
+// 64 entries; the sums are then added across the wave in a fixed order (butterfly), so the
+// result does not depend on timing.
+template <class R, int KP>
+__global__ __launch_bounds__(256) void k_bct_far(int64_t M, const int32_t* __restrict__ off,
                                                  const int32_t* __restrict__ col, const double* __restrict__ nX,
                                                  const double* __restrict__ na, const double* __restrict__ nm,
                                                  double expo, double* __restrict__ yt)
@@ -561,44 +590,68 @@ __global__ __launch_bounds__(256) void k_bct_far(int64_t M, int k, const int32_t
     const int64_t I = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     if (I >= M) return;                       // the whole wave
-    double acc[kMaxGroupCols + 1];
+    double a0 = 0.0, acc[KP];
 #pragma unroll
-    for (int c = 0; c <= kMaxGroupCols; ++c) acc[c] = 0.0;
+    for (int c = 0; c < KP; ++c) acc[c] = 0.0;
     const double xi[3] = {nX[3 * I], nX[3 * I + 1], nX[3 * I + 2]};
     const int32_t e1 = off[I + 1];
     for (int32_t e = off[I] + lane; e < e1; e += 64) {
         const int32_t J = col[e];
+        double m[KP];
+        load_row<KP>(nm + (int64_t)J * KP, m);
         const double w = frac_kernel<R>(xi, nX + 3 * J, expo);
-        acc[0] += w * na[J];
+        a0 += w * na[J];
 #pragma unroll
-        for (int c = 0; c < kMaxGroupCols; ++c)
-            if (c < k) acc[1 + c] += w * nm[(int64_t)J * k + c];
+        for (int c = 0; c < KP; ++c) acc[c] += w * m[c];
     }
+    a0 = wave_sum(a0);
 #pragma unroll
-    for (int c = 0; c <= kMaxGroupCols; ++c) {
-        if (c > k) break;
-        double v = acc[c];
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        acc[c] = v;
-    }
+    for (int c = 0; c < KP; ++c) acc[c] = wave_sum(acc[c]);
     if (lane == 0) {
+        double* y = yt + I * (KP + 4);
+        y[0] = a0;
+        y[1] = 0.0;
+        y[2] = 0.0;
+        y[3] = 0.0;
 #pragma unroll
-        for (int c = 0; c <= kMaxGroupCols; ++c)
-            if (c <= k) yt[I * (k + 1) + c] = acc[c];
+        for (int c = 0; c < KP; ++c) y[4 + c] = acc[c];
     }
+}
+
+// z(S) += ubar_S Y0 - Y over the leaf L's path to the root (downward pass)
+template <int KP>
+__device__ __forceinline__ void bct_down(const double* __restrict__ yt, int64_t P, int64_t L, const double (&us)[KP],
+                                         double (&acc)[KP])
+{
+    double y0 = 0.0, yc[KP];
+#pragma unroll
+    for (int c = 0; c < KP; ++c) yc[c] = 0.0;
+    for (int64_t node = P + L; node >= 1; node >>= 1) {
+        const double* y = yt + node * (KP + 4);
+        double v[KP];
+        load_row<KP>(y + 4, v);
+        y0 += y[0];
+#pragma unroll
+        for (int c = 0; c < KP; ++c) yc[c] += v[c];
+    }
+#pragma unroll
+    for (int c = 0; c < KP; ++c) acc[c] += us[c] * y0 - yc[c];
 }
 
 // Inadmissible (exact) blocks for leaves of at most 8 faces: one wave per row leaf L, lane
 // (i, j) = (lane / 8, lane % 8) takes the pair (face i of L, face j of J) for every leaf J of
-// L's list, all lanes walking the same list; the 8 lanes of face i are then added in a fixed
-// order and lane (i, 0) adds the far field of L's path to the root (downward pass).
-template <class R, class UB>
+// L's list, all lanes walking the same list (64 list entries are read at once and handed
+// out lane by lane; the gathers of U leaves are issued before any of them is used); the 8
+// lanes of face i are then added in a fixed order and lane (i, 0) adds the far field of L's
+// path to the root.
+template <class R, class UB, int KP>
 __global__ __launch_bounds__(256) void k_bct_leaf8(int64_t nF, int leaf, int64_t P, const int32_t* __restrict__ order,
-                                                   const double4* __restrict__ dx, const UB* __restrict__ ub, int kp,
-                                                   int k, const int32_t* __restrict__ noff,
+                                                   const double4* __restrict__ dx, const UB* __restrict__ ub, int k,
+                                                   const int32_t* __restrict__ noff,
                                                    const int32_t* __restrict__ ncol, const double* __restrict__ yt,
                                                    double expo, double* __restrict__ z, int64_t zstride)
 {
+    constexpr int U = 4;
     const int64_t L = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int lane = threadIdx.x & 63;
     const int64_t nleaf = (nF + leaf - 1) / leaf;
@@ -606,48 +659,46 @@ __global__ __launch_bounds__(256) void k_bct_leaf8(int64_t nF, int leaf, int64_t
     const int i = lane >> 3, j = lane & 7;
     const int64_t ps = L * leaf + i;
     const bool own = i < leaf && ps < nF;
-    const int32_t s = own ? order[ps] : -1;
-    double xs[3] = {0.0, 0.0, 0.0}, us[kMaxGroupCols], acc[kMaxGroupCols];
-    if (own) {
-        const double4 X = dx[s];
-        xs[0] = X.x; xs[1] = X.y; xs[2] = X.z;
-    }
-#pragma unroll
-    for (int c = 0; c < kMaxGroupCols; ++c) {
-        us[c] = (own && c < k) ? (double)ub[(int64_t)s * kp + c] : 0.0;
-        acc[c] = 0.0;
-    }
-    // the list in groups of U leaves: the U gathers of a group are issued before any of them
-    // is used, which keeps U memory round trips in flight per lane
-    constexpr int U = 4;
     const bool lane_on = own && j < leaf;
-    const int32_t e0 = noff[L], e1 = noff[L + 1];
-    for (int32_t e = e0; e < e1; e += U) {
-        int32_t t[U];
+    const int32_t s = own ? order[ps] : order[0];
+    const double4 X = dx[s];
+    const double xs[3] = {X.x, X.y, X.z};
+    double us[KP], acc[KP];
+    load_row<KP>(ub + (int64_t)s * KP, us);
 #pragma unroll
-        for (int q = 0; q < U; ++q) {
-            t[q] = -1;
-            if (lane_on && e + q < e1) {
-                const int64_t pt = (int64_t)ncol[e + q] * leaf + j;
-                if (pt < nF) t[q] = order[pt];
+    for (int c = 0; c < KP; ++c) acc[c] = 0.0;
+    const int32_t e0 = noff[L], e1 = noff[L + 1];
+    for (int32_t eb = e0; eb < e1; eb += 64) {
+        const int32_t mine = eb + lane < e1 ? ncol[eb + lane] : 0;
+        const int nb = min(64, e1 - eb);
+        for (int q0 = 0; q0 < nb; q0 += U) {
+            int32_t t[U];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int32_t J = __shfl(mine, q0 + q, 64);
+                const int64_t pt = (int64_t)J * leaf + j;
+                t[q] = (lane_on && q0 + q < nb && pt < nF) ? order[pt] : -1;
+            }
+            double4 Y[U];
+            double ut[U][KP];
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                const int32_t tq = t[q] >= 0 ? t[q] : s;
+                Y[q] = dx[tq];
+                load_row<KP>(ub + (int64_t)tq * KP, ut[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < U; ++q) {
+                if (t[q] < 0 || t[q] == s) continue;
+                const double y[3] = {Y[q].x, Y[q].y, Y[q].z};
+                const double w = frac_kernel<R>(xs, y, expo) * Y[q].w;
+#pragma unroll
+                for (int c = 0; c < KP; ++c) acc[c] += w * (us[c] - ut[q][c]);
             }
         }
-        double4 Y[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) Y[q] = t[q] >= 0 ? dx[t[q]] : make_double4(0.0, 0.0, 0.0, 0.0);
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-            if (t[q] < 0 || t[q] == s) continue;
-            const double y[3] = {Y[q].x, Y[q].y, Y[q].z};
-            const double w = frac_kernel<R>(xs, y, expo) * Y[q].w;
-#pragma unroll
-            for (int c = 0; c < kMaxGroupCols; ++c)
-                if (c < k) acc[c] += w * (us[c] - (double)ub[(int64_t)t[q] * kp + c]);
-        }
     }
 #pragma unroll
-    for (int c = 0; c < kMaxGroupCols; ++c) {
-        if (c >= k) break;
+    for (int c = 0; c < KP; ++c) {
         double v = acc[c];
         v += __shfl_xor(v, 4, 64);
         v += __shfl_xor(v, 2, 64);
@@ -655,24 +706,17 @@ __global__ __launch_bounds__(256) void k_bct_leaf8(int64_t nF, int leaf, int64_t
         acc[c] = v;
     }
     if (!own || j != 0) return;
-    double y0 = 0.0, yc[kMaxGroupCols];
+    bct_down<KP>(yt, P, L, us, acc);
 #pragma unroll
-    for (int c = 0; c < kMaxGroupCols; ++c) yc[c] = 0.0;
-    for (int64_t node = P + L; node >= 1; node >>= 1) {
-        y0 += yt[node * (k + 1)];
-#pragma unroll
-        for (int c = 0; c < kMaxGroupCols; ++c)
-            if (c < k) yc[c] += yt[node * (k + 1) + 1 + c];
-    }
-#pragma unroll
-    for (int c = 0; c < kMaxGroupCols; ++c)
-        if (c < k) z[c * zstride + s] = acc[c] + (us[c] * y0 - yc[c]);
+    for (int c = 0; c < KP; ++c)
+        if (c < k) z[c * zstride + s] = acc[c];
 }
 
-template <class R, class UB>
+// The same for any leaf size: one thread per face, its leaf's list in order.
+template <class R, class UB, int KP>
 __global__ __launch_bounds__(256) void k_bct_faces(int64_t nF, int leaf, int64_t P, const int32_t* __restrict__ order,
-                                                   const double4* __restrict__ dx, const UB* __restrict__ ub, int kp,
-                                                   int k, const int32_t* __restrict__ noff,
+                                                   const double4* __restrict__ dx, const UB* __restrict__ ub, int k,
+                                                   const int32_t* __restrict__ noff,
                                                    const int32_t* __restrict__ ncol, const double* __restrict__ yt,
                                                    double expo, double* __restrict__ z, int64_t zstride)
 {
@@ -681,14 +725,11 @@ __global__ __launch_bounds__(256) void k_bct_faces(int64_t nF, int leaf, int64_t
     const int32_t s = order[p];
     const double4 X = dx[s];
     const double xs[3] = {X.x, X.y, X.z};
-    double us[kMaxGroupCols], acc[kMaxGroupCols];
+    double us[KP], acc[KP];
+    load_row<KP>(ub + (int64_t)s * KP, us);
 #pragma unroll
-    for (int c = 0; c < kMaxGroupCols; ++c) {
-        us[c] = c < k ? (double)ub[(int64_t)s * kp + c] : 0.0;
-        acc[c] = 0.0;
-    }
+    for (int c = 0; c < KP; ++c) acc[c] = 0.0;
     const int64_t L = p / leaf;
-    // near field: the leaves inadmissible for this face's leaf, in list order
     for (int32_t e = noff[L]; e < noff[L + 1]; ++e) {
         const int64_t J = ncol[e];
         const int64_t q1 = min((J + 1) * (int64_t)leaf, nF);
@@ -696,59 +737,41 @@ __global__ __launch_bounds__(256) void k_bct_faces(int64_t nF, int leaf, int64_t
             const int32_t t = order[q];
             if (t == s) continue;
             const double4 Y = dx[t];
+            double ut[KP];
+            load_row<KP>(ub + (int64_t)t * KP, ut);
             const double y[3] = {Y.x, Y.y, Y.z};
             const double w = frac_kernel<R>(xs, y, expo) * Y.w;
 #pragma unroll
-            for (int c = 0; c < kMaxGroupCols; ++c)
-                if (c < k) acc[c] += w * (us[c] - (double)ub[(int64_t)t * kp + c]);
+            for (int c = 0; c < KP; ++c) acc[c] += w * (us[c] - ut[c]);
         }
     }
-    // far field: the leaf's and its ancestors' y~, root last
-    double y0 = 0.0, yc[kMaxGroupCols];
+    bct_down<KP>(yt, P, L, us, acc);
 #pragma unroll
-    for (int c = 0; c < kMaxGroupCols; ++c) yc[c] = 0.0;
-    for (int64_t node = P + L; node >= 1; node >>= 1) {
-        y0 += yt[node * (k + 1)];
-#pragma unroll
-        for (int c = 0; c < kMaxGroupCols; ++c)
-            if (c < k) yc[c] += yt[node * (k + 1) + 1 + c];
-    }
-#pragma unroll
-    for (int c = 0; c < kMaxGroupCols; ++c)
-        if (c < k) z[c * zstride + s] = acc[c] + (us[c] * y0 - yc[c]);
+    for (int c = 0; c < KP; ++c)
+        if (c < k) z[c * zstride + s] = acc[c];
 }
 
-template <class UB>
+template <class UB, int KP>
 hipError_t bct_launch(const BhBuffers& b, const BctLists& bl, int64_t nF, int leaf, bool f64, const FaceData& fd,
-                      const UB* ub, int kp, int k, double expo, double* nm, double* yt, double* z, int64_t zstride,
+                      const UB* ub, int k, double expo, double* nm, double* yt, double* z, int64_t zstride,
                       hipStream_t s)
 {
     int64_t P = 0;
     const int64_t M = (int64_t)bh_node_count(nF, leaf, &P);
-    hipLaunchKernelGGL(k_bh_moment_leaves<UB>, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, s, nF, leaf, P,
-                       b.order, fd.dx, ub, kp, k, nm);
-    hipLaunchKernelGGL(k_bh_moment_levels, dim3(1), dim3(1024), 0, s, P, k, nm);
+    moments_launch<UB, KP>(b, nF, leaf, P, fd, ub, nm, s);
     // one wave (64 lanes) per node for the admissible blocks, per leaf for the exact ones
     const int64_t nleaf = (nF + leaf - 1) / leaf;
     const dim3 gm((unsigned)((M * 64 + 255) / 256)), gl((unsigned)((nleaf * 64 + 255) / 256)),
         gf((unsigned)((nF + 255) / 256)), blk(256);
-    if (f64) {
-        hipLaunchKernelGGL(k_bct_far<double>, gm, blk, 0, s, M, k, bl.far_off, bl.far_col, b.nX, b.na, nm, expo, yt);
-        if (leaf <= 8)
-            hipLaunchKernelGGL((k_bct_leaf8<double, UB>), gl, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
-                               bl.near_off, bl.near_col, yt, expo, z, zstride);
-        else
-            hipLaunchKernelGGL((k_bct_faces<double, UB>), gf, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
-                               bl.near_off, bl.near_col, yt, expo, z, zstride);
-    } else {
-        hipLaunchKernelGGL(k_bct_far<float>, gm, blk, 0, s, M, k, bl.far_off, bl.far_col, b.nX, b.na, nm, expo, yt);
-        if (leaf <= 8)
-            hipLaunchKernelGGL((k_bct_leaf8<float, UB>), gl, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
-                               bl.near_off, bl.near_col, yt, expo, z, zstride);
-        else
-            hipLaunchKernelGGL((k_bct_faces<float, UB>), gf, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, kp, k,
-                               bl.near_off, bl.near_col, yt, expo, z, zstride);
-    }
+    // pair terms in the precision of the face averages (FP64 for TP_PREC_FP64, else FP32)
+    (void)f64;
+    hipLaunchKernelGGL((k_bct_far<UB, KP>), gm, blk, 0, s, M, bl.far_off, bl.far_col, b.nX, b.na, nm, expo, yt);
+    if (leaf <= 8)
+        hipLaunchKernelGGL((k_bct_leaf8<UB, UB, KP>), gl, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, k, bl.near_off,
+                           bl.near_col, yt, expo, z, zstride);
+    else
+        hipLaunchKernelGGL((k_bct_faces<UB, UB, KP>), gf, blk, 0, s, nF, leaf, P, b.order, fd.dx, ub, k, bl.near_off,
+                           bl.near_col, yt, expo, z, zstride);
     return hipGetLastError();
 }
 
@@ -840,25 +863,26 @@ hipError_t launch_bh_frac(const BhBuffers& b, int64_t nF, int leaf, double theta
                           const FaceData& fd, const void* ub, int kp, int k, double* nm, double* z, int64_t zstride,
                           hipStream_t s)
 {
-    if (k < 1 || k > kMaxGroupCols) return hipErrorInvalidValue;
-    const double expo = -(sigma + 1.0);    // |d|^-(2 sigma + 2) = (|d|^2)^-(sigma + 1)
-    if (precision == TP_PREC_FP64)
-        return bh_frac_launch(b, nF, leaf, theta, true, fd, static_cast<const double*>(ub), kp, k, expo, nm, z,
-                              zstride, s);
-    return bh_frac_launch(b, nF, leaf, theta, false, fd, static_cast<const float*>(ub), kp, k, expo, nm, z, zstride,
-                          s);
+    if (k < 1 || k > kMaxGroupCols || kp != (k + 3) / 4 * 4) return hipErrorInvalidValue;
+    const double expo = -(sigma + 1.0);
+    const bool f64 = precision == TP_PREC_FP64;
+#define TP_BHF(T, KP) bh_frac_launch<T, KP>(b, nF, leaf, theta, f64, fd, static_cast<const T*>(ub), k, expo, nm, z, zstride, s)
+    if (f64) return kp == 4 ? TP_BHF(double, 4) : kp == 8 ? TP_BHF(double, 8) : TP_BHF(double, 12);
+    return kp == 4 ? TP_BHF(float, 4) : kp == 8 ? TP_BHF(float, 8) : TP_BHF(float, 12);
+#undef TP_BHF
 }
 
 hipError_t launch_bct_frac(const BhBuffers& b, const BctLists& bl, int64_t nF, int leaf, int precision,
                            double sigma, const FaceData& fd, const void* ub, int kp, int k, double* nm, double* yt,
                            double* z, int64_t zstride, hipStream_t s)
 {
-    if (k < 1 || k > kMaxGroupCols) return hipErrorInvalidValue;
+    if (k < 1 || k > kMaxGroupCols || kp != (k + 3) / 4 * 4) return hipErrorInvalidValue;
     const double expo = -(sigma + 1.0);
-    if (precision == TP_PREC_FP64)
-        return bct_launch(b, bl, nF, leaf, true, fd, static_cast<const double*>(ub), kp, k, expo, nm, yt, z, zstride,
-                          s);
-    return bct_launch(b, bl, nF, leaf, false, fd, static_cast<const float*>(ub), kp, k, expo, nm, yt, z, zstride, s);
+    const bool f64 = precision == TP_PREC_FP64;
+#define TP_BCT(T, KP) bct_launch<T, KP>(b, bl, nF, leaf, f64, fd, static_cast<const T*>(ub), k, expo, nm, yt, z, zstride, s)
+    if (f64) return kp == 4 ? TP_BCT(double, 4) : kp == 8 ? TP_BCT(double, 8) : TP_BCT(double, 12);
+    return kp == 4 ? TP_BCT(float, 4) : kp == 8 ? TP_BCT(float, 8) : TP_BCT(float, 12);
+#undef TP_BCT
 }
 
 }  // namespace tp

@@ -242,8 +242,9 @@ hipError_t launch_bh_eval(const BhBuffers& b, int64_t nF, int leaf, double theta
                           double beta, const FaceData& fd, bool grad, double* gface, int64_t gstride,
                           hipStream_t s);
 // L^sigma's kernel sums with Barnes-Hut (theta > 0) on the built tree: face averages ub
-// ([cap][kp], FP64 for TP_PREC_FP64 else FP32), node moments nm ([2P][k] doubles), output
-// z(S) (the row sums without a_S) at z[c * zstride + S], k <= kMaxGroupCols.
+// ([cap][kp], kp = k rounded up to 4, zero padded; FP64 for TP_PREC_FP64 else FP32), node
+// moments nm ([2P][kp] doubles), output z(S) (the row sums without a_S) at z[c * zstride + S],
+// k <= kMaxGroupCols.
 // Block cluster tree of the fractional operator's kernel matrix (device CSR lists): per row
 // node the admissible column nodes, per row leaf the inadmissible column leaves.
 struct BctLists {
@@ -252,8 +253,8 @@ struct BctLists {
     const int32_t* near_off = nullptr;   // [P + 1] (leaf index = node - P)
     const int32_t* near_col = nullptr;   // leaf indices
 };
-// L^sigma's kernel sums by hierarchical multiplication on the lists; nm [2P][k] node moments,
-// yt [2P][k + 1] far-field values, output as launch_bh_frac.
+// L^sigma's kernel sums by hierarchical multiplication on the lists; nm [2P][kp] node moments,
+// yt [2P][kp + 4] far-field values, output as launch_bh_frac.
 hipError_t launch_bct_frac(const BhBuffers& b, const BctLists& bl, int64_t nF, int leaf, int precision,
                            double sigma, const FaceData& fd, const void* ub, int kp, int k, double* nm, double* yt,
                            double* z, int64_t zstride, hipStream_t s);
