@@ -195,6 +195,8 @@ def parse():
     ap.add_argument("--serve-steps", type=int, default=10)
     ap.add_argument("--serve-capacity-requests", type=int, default=96,
                     help="requests of the saturated serial pass that measures the serial capacity")
+    ap.add_argument("--serve-lane-order", choices=["alternate", "oldest"], default="alternate",
+                    help="batched path: lanes take turns, or the lane with the oldest request goes first")
     ap.add_argument("--serve-saturated", action="store_true",
                     help="also serve the whole mix batched with every request present at t = 0")
     ap.add_argument("--serve-only", action="store_true",
@@ -420,7 +422,8 @@ def serving_meshes(n_req: int, fmax: float, steps: int, seed: int = 0, workers: 
 
 def serving_bench(specs, built, steps: int, fmax: float, seed: int = 0, load: float = 0.8,
                   max_active: int = 16, small_faces: int = 32768, max_large: int = 2,
-                  verbose: bool = False, capacity_requests: int = 0, saturated: bool = True):
+                  verbose: bool = False, capacity_requests: int = 0, saturated: bool = True,
+                  lane_order: str = "alternate"):
     """Continuous batching against the serial one-mesh-at-a-time path on the same requests:
     noisy icospheres / tori with F log-uniform in [2,000, fmax], `steps` descent steps
     each.  The serial path first runs with every request present at t = 0 -- the whole mix,
@@ -448,7 +451,7 @@ def serving_bench(specs, built, steps: int, fmax: float, seed: int = 0, load: fl
     zero = np.zeros(n_req)
     n_cap = n_req if capacity_requests <= 0 else min(n_req, capacity_requests)
     sat_ser = serve.run_serial(requests(zero)[:n_cap], ex, on_done=progress("saturated serial"))
-    lanes = dict(small_faces=small_faces, max_large=max_large)
+    lanes = dict(small_faces=small_faces, max_large=max_large, lane_order=lane_order)
     sat_bat = (serve.run(requests(zero), ex, budget_bytes=200 << 30, max_active=max_active,
                          on_done=progress("saturated batched"), **lanes) if saturated else None)
     cap = n_cap / max(serve.summary(sat_ser)["makespan_s"], 1e-9)      # requests/s
@@ -466,7 +469,9 @@ def serving_bench(specs, built, steps: int, fmax: float, seed: int = 0, load: fl
                      f"area + volume constraints, Armijo), Poisson arrivals at {load} x serial capacity "
                      f"({rate:.2f} requests/s); batched path: meshes of up to {small_faces} faces share "
                      f"steps ({max_active} at most), larger ones ({max_large} admitted at most) step "
-                     f"oldest first, one at a time between the shared steps"),
+                     f"oldest first, one at a time; " +
+                     ("lanes take turns" if lane_order == "alternate" else
+                      "each round goes to the lane whose oldest request arrived first")),
         "serial_capacity_req_per_s": cap,
         "serial_capacity_sample": (f"saturated serial pass over requests 0..{n_cap - 1} "
                                    f"({serve.summary(sat_ser)['makespan_s']:.1f} s)"),
@@ -517,7 +522,7 @@ def main():
     if a.serve_only:
         print(json.dumps(serving_bench(*serve_mesh, a.serve_steps, a.serve_fmax, verbose=True,
                                        capacity_requests=a.serve_capacity_requests,
-                                       saturated=a.serve_saturated)), flush=True)
+                                       saturated=a.serve_saturated, lane_order=a.serve_lane_order)), flush=True)
         return
     dev = torch.device("cuda", 0)
     mesh = mg.workload("torus40k")
@@ -659,7 +664,7 @@ def main():
     if serve_mesh is not None:
         out["serving"] = serving_bench(*serve_mesh, a.serve_steps, a.serve_fmax, verbose=True,
                                        capacity_requests=a.serve_capacity_requests,
-                                       saturated=a.serve_saturated)
+                                       saturated=a.serve_saturated, lane_order=a.serve_lane_order)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(mesh, u_np, a.cpu_seconds)
         out["cpu_baseline"].update(cpu_info())

@@ -112,17 +112,22 @@ class GpuExecutor:
 def run(requests: Sequence[Request], executor, budget_bytes: int, max_active: int = 16,
         clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
         keep_vertices: bool = False, on_done: Optional[Callable[[Result], None]] = None,
-        small_faces: Optional[int] = None, max_large: int = 2) -> List[Result]:
+        small_faces: Optional[int] = None, max_large: int = 2, lane_order: str = "alternate") -> List[Result]:
     """Continuous batching: admit by arrival, slot and memory; shared steps in rounds.
 
     With small_faces None every admitted mesh takes part in every shared step.  With
-    small_faces set, meshes with more faces form a second lane: rounds alternate between one
-    shared step of all admitted small meshes and one step of the oldest admitted large mesh
-    (first come, first served within the lane, so a large request is not slowed down by the
-    large requests admitted after it), and a small mesh's step never waits for more than one
-    large step.  Each lane admits in arrival order (small meshes may overtake large ones);
+    small_faces set, meshes with more faces form a second lane whose round is one step of
+    its oldest admitted mesh (first come, first served within the lane, so a large request
+    is not slowed down by the large requests admitted after it); a small-lane round is one
+    shared step of all admitted small meshes.  lane_order "alternate": the lanes take turns,
+    so a small mesh's step never waits for more than one large step; "oldest": each round
+    goes to the lane whose oldest admitted request arrived first, so requests are served in
+    arrival order as on the serial path while the small ones that are due together share
+    their steps.  Each lane admits in arrival order (small meshes may overtake large ones);
     memory is shared.
     """
+    if lane_order not in ("alternate", "oldest"):
+        raise ValueError("lane_order must be 'alternate' or 'oldest'")
     reqs = sorted(requests, key=lambda r: (r.arrival, r.rid))
     results = {r.rid: Result(r.rid, r.arrival, int(r.F.shape[0])) for r in reqs}
     if small_faces is None:
@@ -167,9 +172,12 @@ def run(requests: Sequence[Request], executor, budget_bytes: int, max_active: in
             if nxt:
                 sleep(max(0.0, min(nxt) - (clock() - t0)))
             continue
-        q = turn % len(lanes)
-        if q not in ready:
-            q = ready[0]
+        if lane_order == "oldest":
+            q = min(ready, key=lambda i: (lanes[i]["active"][0][0].arrival, lanes[i]["active"][0][0].rid))
+        else:
+            q = turn % len(lanes)
+            if q not in ready:
+                q = ready[0]
         turn = q + 1
         ln = lanes[q]
         if ln["one"]:

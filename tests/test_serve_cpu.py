@@ -197,3 +197,29 @@ def test_lanes_bound_small_request_latency():
             # one large step (0.02 s) plus one small batch bounds a small step's latency
             assert lat[policy] < 0.02 + 0.001 + 12 * 8000 * 1e-7 + 1e-3 + 1e-9
     assert lat[50000] < lat[None]
+
+
+def test_lanes_in_arrival_order():
+    # lane_order "oldest": a large request that arrived first runs its steps back to back,
+    # as on the serial path, while the small requests behind it wait and then share steps;
+    # a small request that arrived before the large one goes first
+    V = np.zeros((10, 3))
+    first = serve.Request(0, 0.0, V, np.zeros((3000, 3), np.int32), steps=2)
+    big = serve.Request(1, 0.001, V, np.zeros((200000, 3), np.int32), steps=4)
+    small = [serve.Request(2 + q, 0.002 + 0.001 * q, V, np.zeros((4000, 3), np.int32), steps=2) for q in range(5)]
+    clk = SimClock()
+    ex = FakeExecutor(clk, 10**12)
+    res = serve.run([first, big] + small, ex, budget_bytes=10**12, max_active=16, clock=clk, sleep=clk.sleep,
+                    small_faces=50000, lane_order="oldest")
+    by = {r.rid: r for r in res}
+    assert all(r.status == 0 for r in res)
+    # the large request's steps are consecutive batches of one
+    big_rounds = [i for i, b in enumerate(ex.batches) if b == [1]]
+    assert big_rounds == list(range(big_rounds[0], big_rounds[0] + 4))
+    # the first small request is stepped before the large one starts
+    assert by[0].step_done[0] < by[1].step_done[0]
+    # the later small ones start after the large one is done and share their steps
+    assert all(by[r].step_done[0] > by[1].finished for r in range(2, 7))
+    assert any(len(b) >= 5 for b in ex.batches)
+    with pytest.raises(ValueError):
+        serve.run(small, ex, budget_bytes=10**12, small_faces=50000, lane_order="lifo")
