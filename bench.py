@@ -195,7 +195,7 @@ def parse():
     ap.add_argument("--serve-steps", type=int, default=10)
     ap.add_argument("--serve-capacity-requests", type=int, default=96,
                     help="requests of the saturated serial pass that measures the serial capacity")
-    ap.add_argument("--serve-lane-order", choices=["alternate", "oldest"], default="alternate",
+    ap.add_argument("--serve-lane-order", choices=["alternate", "oldest"], default="oldest",
                     help="batched path: lanes take turns, or the lane with the oldest request goes first")
     ap.add_argument("--serve-saturated", action="store_true",
                     help="also serve the whole mix batched with every request present at t = 0")
@@ -423,7 +423,7 @@ def serving_meshes(n_req: int, fmax: float, steps: int, seed: int = 0, workers: 
 def serving_bench(specs, built, steps: int, fmax: float, seed: int = 0, load: float = 0.8,
                   max_active: int = 16, small_faces: int = 32768, max_large: int = 2,
                   verbose: bool = False, capacity_requests: int = 0, saturated: bool = True,
-                  lane_order: str = "alternate"):
+                  lane_order: str = "oldest"):
     """Continuous batching against the serial one-mesh-at-a-time path on the same requests:
     noisy icospheres / tori with F log-uniform in [2,000, fmax], `steps` descent steps
     each.  The serial path first runs with every request present at t = 0 -- the whole mix,
@@ -454,6 +454,10 @@ def serving_bench(specs, built, steps: int, fmax: float, seed: int = 0, load: fl
     lanes = dict(small_faces=small_faces, max_large=max_large, lane_order=lane_order)
     sat_bat = (serve.run(requests(zero), ex, budget_bytes=200 << 30, max_active=max_active,
                          on_done=progress("saturated batched"), **lanes) if saturated else None)
+    # the batched path saturated on the same sample as the serial capacity pass
+    sample_bat = (serve.run(requests(zero)[:n_cap], ex, budget_bytes=200 << 30, max_active=max_active,
+                            on_done=progress("saturated batched sample"), **lanes)
+                  if not saturated and n_cap < n_req else None)
     cap = n_cap / max(serve.summary(sat_ser)["makespan_s"], 1e-9)      # requests/s
     rate = load * cap
     arr = mg.poisson_arrivals(n_req, rate, seed + 1)
@@ -485,6 +489,11 @@ def serving_bench(specs, built, steps: int, fmax: float, seed: int = 0, load: fl
     if sat_bat is not None:
         out["saturated"] = {"batched": serve.summary(sat_bat),
                             "serial": serve.summary(sat_ser), "note": "serial: the capacity sample"}
+    if sample_bat is not None:
+        out["saturated_sample"] = {"requests": n_cap, "batched": serve.summary(sample_bat),
+                                   "serial": serve.summary(sat_ser),
+                                   "steps_per_s": {"batched": serve.summary(sample_bat)["steps_per_s"],
+                                                   "serial": serve.summary(sat_ser)["steps_per_s"]}}
     return out
 
 

@@ -224,3 +224,23 @@ def test_obstacle_bh_step(tp):
         r = P.step()
         assert P.obstacle_stats()[0] > 0
     assert r.E_new < r.E and r.slope < 0
+
+
+@pytest.mark.parametrize("leaf,k", [(8, 5), (12, 3), (5, 9), (16, 7)])
+def test_tree_fractional_shapes(tp, leaf, k):
+    """The tree fractional applies for other leaf sizes (the per-face kernel above 8 faces
+    per leaf, ragged leaves) and column counts (rows padded to 8 and 12), against the
+    oracle's Barnes-Hut and block-by-block products on the same tree (FP64 pair terms)."""
+    import oracle as O
+    m = mg.add_noise(mg.geodesic_sphere(9), 0.01, 1)          # 1620 faces
+    u = mg.random_columns(m.nV, k, 11)
+    print(f"[bh] tree fractional leaf={leaf} k={k}", flush=True)
+    Lb = O.bh_fractional_apply(m.V, m.F, u, 0.5, leaf=leaf)
+    Lc, cnt = O.bct_fractional_apply(m.V, m.F, u, 0.5, leaf=leaf)
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32), tp.default_params(precision=2, theta=0.5, leaf_size=leaf)) as P:
+        L1 = P.fractional_apply(dev(u)).cpu().numpy()
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32), tp.default_params(precision=2, chi=0.5, leaf_size=leaf)) as P:
+        L2 = P.fractional_apply(dev(u)).cpu().numpy()
+        assert tuple(P.bct_stats()) == cnt
+    assert np.linalg.norm(L1 - Lb) <= 1e-12 * np.linalg.norm(Lb)
+    assert np.linalg.norm(L2 - Lc) <= 1e-12 * np.linalg.norm(Lc)
