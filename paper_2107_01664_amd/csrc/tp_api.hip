@@ -1385,50 +1385,26 @@ tp_status enqueue_cg(const Batch& B, double* const* b, double* const* x, int k, 
             if (A->last_iters != Q->last_iters) return A->last_iters > Q->last_iters;
             return A->pcg.nb > Q->pcg.nb;
         });
-        // Column groups: a 6- or 9-column solve runs as 2 or 3 independent 3-column systems
-        // in the same cooperative launch when all their workgroups are resident together
-        // (an iteration of 3 columns takes about half the time of one of 9, and the groups
-        // run side by side); otherwise as groups of up to kMaxGroupCols columns, one launch
-        // per group.  Each column's arithmetic is the same either way.
-        int gw = std::min(k, kMaxGroupCols);
-        if (k > 3 && k % 3 == 0 && k <= kMaxGroupCols && (size_t)(k / 3) * kBarWordsPerGroup <= cg_bar_words(k)) {
-            int64_t blocks = 0;
-            int nb_max = 0;
-            for (size_t m : pc) {
-                blocks += (int64_t)(k / 3) * B[m]->pcg.nb;
-                nb_max = std::max(nb_max, B[m]->pcg.nb);
-            }
-            if (blocks <= pcg_batch_capacity(3, nb_max)) gw = 3;
-        }
-        const int ng = gw < k && gw == 3 ? k / 3 : 1;      // groups that share one launch
-        std::vector<PcgItem> items(pc.size() * ng);
-        for (int c0 = 0; c0 < k; c0 += gw * ng) {
-            const int kc = std::min(gw, k - c0);
+        std::vector<PcgItem> items(pc.size());
+        for (int c0 = 0; c0 < k; c0 += kMaxGroupCols) {
+            const int kc = std::min(kMaxGroupCols, k - c0);
             for (size_t q = 0; q < pc.size(); ++q) {
                 tp_problem* P = B[pc[q]];
-                const size_t n = (size_t)P->nV;
-                for (int g = 0; g < ng; ++g) {
-                    const int cg = c0 + g * kc;            // first column of this group
-                    double* bp = P->pcg_bp.p + g * n * kc;
-                    double* xp = P->pcg_xp.p + g * n * kc;
-                    TP_HIP(launch_permute_rows(P->nV, kc, P->pcg.perm, k, cg, b[pc[q]], bp, true, s));
-                    PcgItem& it = items[q * ng + g];
-                    it.ps = &P->pcg;
-                    it.b = bp;
-                    it.x = xp;
-                    // warm start: x[m] still holds this solve's solution of the last step
-                    it.warm = warm && P->warm_now ? 1 : 0;
-                    if (it.warm) TP_HIP(launch_permute_rows(P->nV, kc, P->pcg.perm, k, cg, x[pc[q]], xp, true, s));
-                    it.w.Vb = P->pcg_Vb.p + g * 2 * n * kc;
-                    it.w.rho = P->pcg_rho.p + (size_t)g * 2 * P->pcg.nb * 4 * kc;
-                    it.w.red = P->pcg_red.p + (size_t)g * 2 * P->pcg.nb * 3 * kc;
-                    it.w.bar = P->cg_bar.p + (size_t)g * kBarWordsPerGroup;
-                    it.w.flags = P->flags.p;
-                    it.w.iters = P->cg_iters.p + cg;
-                    it.w.relres = P->cg_relres.p + cg;
-                    it.rtol = P->prm.cg_rtol;
-                    it.maxiter = P->prm.cg_maxiter;
-                }
+                TP_HIP(launch_permute_rows(P->nV, kc, P->pcg.perm, k, c0, b[pc[q]], P->pcg_bp.p, true, s));
+                PcgItem& it = items[q];
+                it.ps = &P->pcg;
+                it.b = P->pcg_bp.p;
+                it.x = P->pcg_xp.p;
+                // warm start: x[m] still holds this solve's solution of the last step
+                it.warm = warm && P->warm_now ? 1 : 0;
+                if (it.warm)
+                    TP_HIP(launch_permute_rows(P->nV, kc, P->pcg.perm, k, c0, x[pc[q]], P->pcg_xp.p, true, s));
+                it.w.Vb = P->pcg_Vb.p; it.w.rho = P->pcg_rho.p; it.w.red = P->pcg_red.p;
+                it.w.bar = P->cg_bar.p; it.w.flags = P->flags.p;
+                it.w.iters = P->cg_iters.p + c0;
+                it.w.relres = P->cg_relres.p + c0;
+                it.rtol = P->prm.cg_rtol;
+                it.maxiter = P->prm.cg_maxiter;
             }
             void *tdev = nullptr, *thost = nullptr;
             int slot = 0;
@@ -1438,10 +1414,7 @@ tp_status enqueue_cg(const Batch& B, double* const* b, double* const* x, int k, 
             B[0]->tab.used[slot] = true;
             for (size_t q = 0; q < pc.size(); ++q) {
                 tp_problem* P = B[pc[q]];
-                const size_t n = (size_t)P->nV;
-                for (int g = 0; g < ng; ++g)
-                    TP_HIP(launch_permute_rows(P->nV, kc, P->pcg.perm, k, c0 + g * kc, P->pcg_xp.p + g * n * kc,
-                                               x[pc[q]], false, s));
+                TP_HIP(launch_permute_rows(P->nV, kc, P->pcg.perm, k, c0, P->pcg_xp.p, x[pc[q]], false, s));
             }
         }
     }

@@ -1231,52 +1231,29 @@ int pcg_max_coarse() { return kCoarseMax; }
 int pcg_max_block_aggregates() { return kMaxAggNbn; }
 size_t pcg_table_bytes(int n) { return sizeof(PcgArgs) * (size_t)std::max(n, 1); }
 
-// Dynamic LDS of a launch whose largest problem has nb_max blocks (the block shares are
-// staged in LDS when they fit beside PcgShared) and the number of its workgroups that are
-// resident at once on the device.
-static hipError_t pcg_launch_shape(int k, int nb_max, size_t* smem_out, bool* stage_out, int64_t* cap_out)
-{
-    const void* fn = pcg_fn(k);
-    if (!fn) return hipErrorInvalidValue;
-    const size_t base = (pcg_smem_bytes(k) + 15) / 16 * 16;
-    const size_t stage_bytes = sizeof(double) * (size_t)nb_max * 4 * (size_t)k;
-    int lds_max = 0;
-    hipError_t e = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device_info().device);
-    if (e != hipSuccess) return e;
-    const bool stage = base + stage_bytes <= (size_t)lds_max;
-    const size_t smem = stage ? base + stage_bytes : pcg_smem_bytes(k);
-    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
-    if (e != hipSuccess) return e;
-    int per_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, smem);
-    if (e != hipSuccess) return e;
-    *smem_out = smem;
-    *stage_out = stage;
-    *cap_out = (int64_t)per_cu * device_info().num_cu;
-    return hipSuccess;
-}
-
-int64_t pcg_batch_capacity(int k, int nb_max)
-{
-    size_t smem = 0;
-    bool stage = false;
-    int64_t cap = 0;
-    return pcg_launch_shape(k, nb_max, &smem, &stage, &cap) == hipSuccess ? cap : 0;
-}
-
 hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, void* tab_host,
                             hipStream_t s)
 {
     if (n < 1) return hipSuccess;
     const void* fn = pcg_fn(k);
     if (!fn) return hipErrorInvalidValue;
+    // LDS staging of the block shares when the largest problem's fit beside PcgShared
+    hipError_t e0;
     int nb_max = 0;
     for (int m = 0; m < n; ++m) nb_max = std::max(nb_max, items[m].ps->nb);
-    size_t smem = 0;
-    bool stage = false;
-    int64_t cap = 0;
-    hipError_t e = pcg_launch_shape(k, nb_max, &smem, &stage, &cap);
+    const size_t base = (pcg_smem_bytes(k) + 15) / 16 * 16;
+    const size_t stage_bytes = sizeof(double) * (size_t)nb_max * 4 * (size_t)k;
+    int lds_max = 0;
+    e0 = hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, device_info().device);
+    if (e0 != hipSuccess) return e0;
+    const bool stage = base + stage_bytes <= (size_t)lds_max;
+    const size_t smem = stage ? base + stage_bytes : pcg_smem_bytes(k);
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
+    int per_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kThreads, smem);
+    if (e != hipSuccess) return e;
+    const int64_t cap = (int64_t)per_cu * device_info().num_cu;
     PcgArgs* H = static_cast<PcgArgs*>(tab_host);
     for (int m = 0; m < n; ++m) {
         const PcgItem& it = items[m];

@@ -97,9 +97,6 @@ size_t pcg_table_bytes(int n);
 // as fit on the device at once; each system's arithmetic is that of a launch of its own.
 hipError_t launch_pcg_batch(const PcgItem* items, int n, int k, void* tab_dev, void* tab_host,
                             hipStream_t s);
-// Workgroups of k-column systems (largest nb_max blocks) resident at once, i.e. how many
-// blocks launch_pcg_batch can put into one cooperative launch (0 on error).
-int64_t pcg_batch_capacity(int k, int nb_max);
 
 // Multi-launch form of the same solve for problems of more than pcg_max_blocks() blocks
 // (up to pcg_max_blocks_multi()): one kernel per phase of an iteration, the host reading

@@ -488,25 +488,6 @@ def test_pcg_columns_together_like_alone(tp, torus40k):
     assert rep.cg_iters[0] <= max(alone) + 5
 
 
-def test_pcg_column_groups(tp, meshes, torus40k):
-    """A 9-column (or 6-column) solve runs as independent 3-column systems sharing one
-    cooperative launch when their workgroups fit on the device at once: the result of each
-    group of three columns is then exactly that of solving those three columns alone."""
-    for m in (meshes["small_sphere"], torus40k):
-        b = mg.random_columns(m.nV, 9, 5)
-        with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
-            x9, rep9 = P.poisson_solve(dev(b))
-            x6, _ = P.poisson_solve(dev(b[:, :6]))
-            for g in range(3):
-                x3, rep3 = P.poisson_solve(dev(b[:, 3 * g:3 * g + 3]))
-                d9 = (x9[:, 3 * g:3 * g + 3] - x3).abs().max().item()
-                print(f"[pcg] nV={m.nV} group {g}: 9 vs 3 columns max diff {d9:.2e}", flush=True)
-                assert rel(x9[:, 3 * g:3 * g + 3].cpu().numpy(), x3.cpu().numpy()) <= 1e-9
-                if g < 2:
-                    assert rel(x6[:, 3 * g:3 * g + 3].cpu().numpy(), x3.cpu().numpy()) <= 1e-9
-            assert rep9.cg_relres[0] <= 1e-10
-
-
 # ---------------------------------------------------- inner-product operator A = B + B0
 
 S_SOB = 5.0 / 3.0   # s = (beta - 2) / alpha for alpha = 6, beta = 12
