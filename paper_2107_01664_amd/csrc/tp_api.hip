@@ -3,6 +3,7 @@
 #include "tp_solver.h"
 #include "tp_sobolev.h"
 #include "tp_obstacle.h"
+#include "tp_tree.h"
 
 #include <algorithm>
 #include <cmath>
@@ -141,6 +142,14 @@ struct DevBuf {
         fr_user = nullptr;
     }
     size_t bytes() const { return n * sizeof(T); }
+    void swap(DevBuf& o)
+    {
+        std::swap(p, o.p);
+        std::swap(n, o.n);
+        std::swap(fr, o.fr);
+        std::swap(fr_user, o.fr_user);
+        std::swap(fr_stream, o.fr_stream);
+    }
     // Grow to at least cnt elements (contents are not preserved).
     tp_status ensure(size_t cnt, hipStream_t s)
     {
@@ -379,6 +388,10 @@ struct tp_problem {
     // block cluster tree (chi > 0): device CSR lists, far-field values [2P][k + 1], the
     // geometry version they describe and their block counts
     DevBuf<int32_t> bct_far_off, bct_far_col, bct_near_off, bct_near_col;
+    DevBuf<uint64_t> bct_fr0, bct_fr1, bct_fkeys, bct_nkeys, bct_sorted, bct_grow;
+    DevBuf<char> bct_tmp;
+    DevBuf<unsigned long long> bct_cnt;
+    HostBuf<unsigned long long> bct_hcnt;
     DevBuf<double> bct_yt;
     int64_t bct_ver = -1, bct_nadm = 0, bct_ninad = 0;
     DevBuf<double> bh_flo, bh_fhi, bh_fr2, bh_box, bh_na, bh_nsx, bh_nX, bh_nlo, bh_nhi, bh_nr2, bh_gS, bh_eS,
@@ -438,7 +451,9 @@ struct tp_problem {
              bh_nX.bytes() + bh_nlo.bytes() + bh_nhi.bytes() + bh_nr2.bytes() + bh_gS.bytes() + bh_eS.bytes() +
              bh_accF.bytes() + bh_accN.bytes() + bh_kin.bytes() + bh_kout.bytes() + bh_tmp.bytes() +
              bh_order.bytes() + bh_pos.bytes() + bh_counts.bytes() + bh_nm.bytes() + bct_far_off.bytes() +
-             bct_far_col.bytes() + bct_near_off.bytes() + bct_near_col.bytes() + bct_yt.bytes();
+             bct_far_col.bytes() + bct_near_off.bytes() + bct_near_col.bytes() + bct_yt.bytes() +
+             bct_fr0.bytes() + bct_fr1.bytes() + bct_fkeys.bytes() + bct_nkeys.bytes() + bct_sorted.bytes() +
+             bct_grow.bytes() + bct_tmp.bytes() + bct_cnt.bytes();
         b += ng_kin.bytes() + ng_kout.bytes() + ng_vin.bytes() + ng_vout.bytes() + ng_sfx.bytes() + ng_sfl.bytes() +
              ng_cell.bytes() + ng_tmp.bytes() + ng_prm.bytes();
         return b;
@@ -966,6 +981,19 @@ tp_status ensure_tree(tp_problem* P)
 // a pair of clusters is admissible when max(r_I^2, r_J^2) < chi^2 dist^2 (dist between the
 // boxes), otherwise it is split into its children's pairs until both are leaves (all
 // leaves lie at the same depth); empty clusters (padding) are dropped.
+// Grow buf to at least need elements, keeping its first used ones (tmp: spare buffer).
+tp_status grow_keep(DevBuf<uint64_t>& buf, DevBuf<uint64_t>& tmp, size_t used, size_t need, hipStream_t s)
+{
+    if (need <= buf.n && buf.p) return TP_OK;
+    TP_TRY(tmp.ensure(std::max(need, buf.n + buf.n / 2), s));
+    if (used) TP_HIP(hipMemcpyAsync(tmp.p, buf.p, sizeof(uint64_t) * used, hipMemcpyDeviceToDevice, s));
+    buf.swap(tmp);
+    return TP_OK;
+}
+
+// Block lists of the block cluster tree of the current tree (once per geometry), built on
+// the device level by level (the block counts of each level are read back to size the
+// next), then sorted into CSR rows.
 tp_status ensure_bct(tp_problem* P)
 {
     TP_TRY(ensure_tree(P));
@@ -973,70 +1001,50 @@ tp_status ensure_bct(tp_problem* P)
     hipStream_t s = P->stream;
     int64_t Pl = 0;
     const int64_t M = (int64_t)bh_node_count(P->nF, P->prm.leaf_size, &Pl);
-    std::vector<double> na(M), nlo(3 * M), nhi(3 * M), nr2(M);
-    TP_HIP(hipMemcpyAsync(na.data(), P->bh.na, sizeof(double) * M, hipMemcpyDeviceToHost, s));
-    TP_HIP(hipMemcpyAsync(nlo.data(), P->bh.nlo, sizeof(double) * 3 * M, hipMemcpyDeviceToHost, s));
-    TP_HIP(hipMemcpyAsync(nhi.data(), P->bh.nhi, sizeof(double) * 3 * M, hipMemcpyDeviceToHost, s));
-    TP_HIP(hipMemcpyAsync(nr2.data(), P->bh.nr2, sizeof(double) * M, hipMemcpyDeviceToHost, s));
+    TP_TRY(P->bct_cnt.ensure(3, s));
+    TP_TRY(P->bct_hcnt.ensure(3));
+    TP_TRY(P->bct_fr0.ensure(1024, s));
+    const uint64_t root = (1ull << 32) | 1ull;
+    TP_HIP(hipMemcpyAsync(P->bct_fr0.p, &root, sizeof(root), hipMemcpyHostToDevice, s));
     TP_HIP(hipStreamSynchronize(s));
-    const double chi2 = P->prm.chi * P->prm.chi;
-    auto separated = [&](int64_t I, int64_t J) {
-        double d2 = 0.0;
-        for (int m = 0; m < 3; ++m) {
-            const double g1 = nlo[3 * J + m] - nhi[3 * I + m];
-            const double g2 = nlo[3 * I + m] - nhi[3 * J + m];
-            double g = g1 > g2 ? g1 : g2;
-            g = g < 0.0 ? 0.0 : g;
-            d2 = d2 + g * g;
-        }
-        const double r2 = nr2[I] > nr2[J] ? nr2[I] : nr2[J];
-        return r2 < chi2 * d2;
-    };
-    std::vector<std::vector<int32_t>> far(M), near(Pl);
-    std::vector<std::pair<int64_t, int64_t>> cur{{1, 1}}, next;
-    int64_t nadm = 0, ninad = 0;
-    while (!cur.empty()) {
-        next.clear();
-        for (const auto& pr : cur) {
-            const int64_t I = pr.first, J = pr.second;
-            if (!(na[I] > 0.0) || !(na[J] > 0.0)) continue;
-            if (separated(I, J)) {
-                far[I].push_back((int32_t)J);
-                ++nadm;
-            } else if (I >= Pl) {
-                near[I - Pl].push_back((int32_t)(J - Pl));
-                ++ninad;
-            } else {
-                for (int e = 0; e < 2; ++e)
-                    for (int f = 0; f < 2; ++f) next.emplace_back(2 * I + e, 2 * J + f);
-            }
-        }
-        cur.swap(next);
+    DevBuf<uint64_t>* cur = &P->bct_fr0;
+    DevBuf<uint64_t>* nxt = &P->bct_fr1;
+    int64_t n = 1, nfar = 0, nnear = 0;
+    while (n > 0) {
+        TP_TRY(nxt->ensure((size_t)4 * n, s));
+        TP_TRY(grow_keep(P->bct_fkeys, P->bct_grow, (size_t)nfar, (size_t)(nfar + n), s));
+        TP_TRY(grow_keep(P->bct_nkeys, P->bct_grow, (size_t)nnear, (size_t)(nnear + n), s));
+        unsigned long long* h = P->bct_hcnt.p;
+        h[0] = (unsigned long long)nfar;
+        h[1] = (unsigned long long)nnear;
+        h[2] = 0;
+        TP_HIP(hipMemcpyAsync(P->bct_cnt.p, h, 3 * sizeof(unsigned long long), hipMemcpyHostToDevice, s));
+        TP_HIP(launch_bct_expand(P->bh, Pl, P->prm.chi, cur->p, n, P->bct_fkeys.p, P->bct_nkeys.p, nxt->p,
+                                 P->bct_cnt.p, s));
+        TP_HIP(hipMemcpyAsync(h, P->bct_cnt.p, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+        TP_HIP(hipStreamSynchronize(s));
+        nfar = (int64_t)h[0];
+        nnear = (int64_t)h[1];
+        n = (int64_t)h[2];
+        std::swap(cur, nxt);
     }
-    auto to_csr = [](const std::vector<std::vector<int32_t>>& rows, std::vector<int32_t>& off,
-                     std::vector<int32_t>& col) {
-        off.assign(rows.size() + 1, 0);
-        for (size_t r = 0; r < rows.size(); ++r) off[r + 1] = off[r] + (int32_t)rows[r].size();
-        col.clear();
-        col.reserve(off.back());
-        for (const auto& r : rows) col.insert(col.end(), r.begin(), r.end());
-        if (col.empty()) col.push_back(0);
-    };
-    std::vector<int32_t> foff, fcol, noff, ncol;
-    to_csr(far, foff, fcol);
-    to_csr(near, noff, ncol);
-    TP_TRY(P->bct_far_off.ensure(foff.size(), s));
-    TP_TRY(P->bct_far_col.ensure(fcol.size(), s));
-    TP_TRY(P->bct_near_off.ensure(noff.size(), s));
-    TP_TRY(P->bct_near_col.ensure(ncol.size(), s));
+    if (nfar > (int64_t)INT32_MAX || nnear > (int64_t)INT32_MAX)
+        return fail(TP_E_OUT_OF_MEMORY, "block cluster tree: more than 2^31 blocks");
+    const int64_t nmax = std::max<int64_t>(std::max(nfar, nnear), 1);
+    TP_TRY(P->bct_sorted.ensure((size_t)nmax, s));
+    const size_t tb = bct_sort_temp_bytes(nmax);
+    TP_TRY(P->bct_tmp.ensure(tb, s));
+    TP_TRY(P->bct_far_off.ensure((size_t)M + 1, s));
+    TP_TRY(P->bct_far_col.ensure((size_t)std::max<int64_t>(nfar, 1), s));
+    TP_TRY(P->bct_near_off.ensure((size_t)Pl + 1, s));
+    TP_TRY(P->bct_near_col.ensure((size_t)std::max<int64_t>(nnear, 1), s));
     TP_TRY(P->bct_yt.ensure((size_t)M * ((kMaxGroupCols + 3) / 4 * 4 + 4), s));
-    TP_HIP(hipMemcpyAsync(P->bct_far_off.p, foff.data(), sizeof(int32_t) * foff.size(), hipMemcpyHostToDevice, s));
-    TP_HIP(hipMemcpyAsync(P->bct_far_col.p, fcol.data(), sizeof(int32_t) * fcol.size(), hipMemcpyHostToDevice, s));
-    TP_HIP(hipMemcpyAsync(P->bct_near_off.p, noff.data(), sizeof(int32_t) * noff.size(), hipMemcpyHostToDevice, s));
-    TP_HIP(hipMemcpyAsync(P->bct_near_col.p, ncol.data(), sizeof(int32_t) * ncol.size(), hipMemcpyHostToDevice, s));
-    TP_HIP(hipStreamSynchronize(s));    // the host vectors go out of scope
-    P->bct_nadm = nadm;
-    P->bct_ninad = ninad;
+    TP_HIP(launch_bct_sort_csr(P->bct_fkeys.p, P->bct_sorted.p, nfar, P->bct_tmp.p, tb, M, P->bct_far_off.p,
+                               P->bct_far_col.p, s));
+    TP_HIP(launch_bct_sort_csr(P->bct_nkeys.p, P->bct_sorted.p, nnear, P->bct_tmp.p, tb, Pl, P->bct_near_off.p,
+                               P->bct_near_col.p, s));
+    P->bct_nadm = nfar;
+    P->bct_ninad = nnear;
     P->bct_ver = P->geom_ver;
     return TP_OK;
 }

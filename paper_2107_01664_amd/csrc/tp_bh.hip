@@ -775,6 +775,74 @@ hipError_t bct_launch(const BhBuffers& b, const BctLists& bl, int64_t nF, int le
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- block cluster tree lists
+//
+// The blocks of the fractional operator's kernel matrix, built on the device by a
+// breadth-first split of (root, root): a pair of nodes of one depth is an admissible block
+// when separated, an exact block when it is a pair of leaves, else its four pairs of
+// children go to the next level.  Appends use atomic counters, so the order in which a
+// level's blocks land is arbitrary; the lists are then sorted by (row, column), which fixes
+// them.  The separation test repeats the reading's arithmetic in FP64 without fused
+// multiply-adds, as for the Barnes-Hut admissibility.
+__device__ __forceinline__ bool bct_separated(const double* __restrict__ nlo, const double* __restrict__ nhi,
+                                              const double* __restrict__ nr2, int64_t I, int64_t J, double chi2)
+{
+    double d2 = 0.0;
+    for (int m = 0; m < 3; ++m) {
+        const double g1 = nlo[3 * J + m] - nhi[3 * I + m];
+        const double g2 = nlo[3 * I + m] - nhi[3 * J + m];
+        double g = g1 > g2 ? g1 : g2;
+        g = g < 0.0 ? 0.0 : g;
+        d2 = d2 + g * g;
+    }
+    const double r2 = nr2[I] > nr2[J] ? nr2[I] : nr2[J];
+    return r2 < chi2 * d2;
+}
+
+// cnt[0], cnt[1]: admissible and exact blocks so far (appended at these positions);
+// cnt[2]: pairs of the next level.
+__global__ void k_bct_expand(const uint64_t* __restrict__ cur, int64_t n, const double* __restrict__ na,
+                             const double* __restrict__ nlo, const double* __restrict__ nhi,
+                             const double* __restrict__ nr2, int64_t P, double chi2, uint64_t* __restrict__ far,
+                             uint64_t* __restrict__ near, uint64_t* __restrict__ next,
+                             unsigned long long* __restrict__ cnt)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= n) return;
+    const uint64_t key = cur[e];
+    const int64_t I = (int64_t)(key >> 32), J = (int64_t)(key & 0xffffffffull);
+    if (!(na[I] > 0.0) || !(na[J] > 0.0)) return;
+    if (bct_separated(nlo, nhi, nr2, I, J, chi2)) {
+        far[atomicAdd(&cnt[0], 1ull)] = key;
+    } else if (I >= P) {                        // two leaves (pairs stay on one depth)
+        near[atomicAdd(&cnt[1], 1ull)] = ((uint64_t)(I - P) << 32) | (uint64_t)(J - P);
+    } else {
+        const unsigned long long o = atomicAdd(&cnt[2], 4ull);
+        for (int a = 0; a < 2; ++a)
+            for (int c = 0; c < 2; ++c)
+                next[o + 2 * a + c] = ((uint64_t)(2 * I + a) << 32) | (uint64_t)(2 * J + c);
+    }
+}
+
+// CSR of sorted (row << 32 | column) keys: off[r] = first key of row r (r = 0 .. rows),
+// col[e] = column of key e.
+__global__ void k_bct_csr(const uint64_t* __restrict__ keys, int64_t n, int64_t rows, int32_t* __restrict__ off,
+                          int32_t* __restrict__ col)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t <= rows) {
+        const uint64_t target = (uint64_t)t << 32;
+        int64_t lo = 0, hi = n;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (keys[mid] < target) lo = mid + 1;
+            else hi = mid;
+        }
+        off[t] = (int32_t)lo;
+    }
+    if (t < n) col[t] = (int32_t)(keys[t] & 0xffffffffull);
+}
+
 }  // namespace
 
 size_t bh_node_count(int64_t nF, int leaf, int64_t* P_out)
@@ -883,6 +951,37 @@ hipError_t launch_bct_frac(const BhBuffers& b, const BctLists& bl, int64_t nF, i
     if (f64) return kp == 4 ? TP_BCT(double, 4) : kp == 8 ? TP_BCT(double, 8) : TP_BCT(double, 12);
     return kp == 4 ? TP_BCT(float, 4) : kp == 8 ? TP_BCT(float, 8) : TP_BCT(float, 12);
 #undef TP_BCT
+}
+
+size_t bct_sort_temp_bytes(int64_t n)
+{
+    size_t bytes = 0;
+    (void)hipcub::DeviceRadixSort::SortKeys(nullptr, bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                            (int)std::max<int64_t>(n, 1), 0, 64);
+    return bytes;
+}
+
+hipError_t launch_bct_expand(const BhBuffers& b, int64_t P, double chi, const uint64_t* cur, int64_t n, uint64_t* far,
+                             uint64_t* near, uint64_t* next, unsigned long long* cnt, hipStream_t s)
+{
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_bct_expand, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cur, n, b.na, b.nlo, b.nhi,
+                       b.nr2, P, chi * chi, far, near, next, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_bct_sort_csr(const uint64_t* keys, uint64_t* sorted, int64_t n, void* tmp, size_t tmp_bytes,
+                               int64_t rows, int32_t* off, int32_t* col, hipStream_t s)
+{
+    if (n > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    if (n > 0) {
+        size_t tb = tmp_bytes;
+        hipError_t e = hipcub::DeviceRadixSort::SortKeys(tmp, tb, keys, sorted, (int)n, 0, 64, s);
+        if (e != hipSuccess) return e;
+    }
+    const int64_t m = std::max(rows + 1, n);
+    hipLaunchKernelGGL(k_bct_csr, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, sorted, n, rows, off, col);
+    return hipGetLastError();
 }
 
 }  // namespace tp

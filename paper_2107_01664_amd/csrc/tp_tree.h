@@ -9,11 +9,26 @@
 // skips the node's subtree while the wave walks it for other lanes.  Lanes without a face
 // (live = false) take no node.  All lanes of the wave must call this together.
 #pragma once
+#include "tp_internal.h"
+#include "tp_solver.h"   // wave_sum: a wave-wide sum in a fixed order
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
 
 namespace tp {
+
+// Block lists of the block cluster tree, built on the device (tp_bh.hip): one level of the
+// breadth-first split per launch_bct_expand (pairs of nodes of one depth as (I << 32 | J);
+// admissible blocks appended to far at cnt[0], exact leaf blocks (as leaf indices) to near
+// at cnt[1], the next level's pairs to next at cnt[2]; the caller sizes far and near for
+// n more entries and next for 4n), then launch_bct_sort_csr turns a list into CSR rows
+// (sorted by row and column; off [rows + 1], col [n]).
+size_t bct_sort_temp_bytes(int64_t n);
+hipError_t launch_bct_expand(const BhBuffers& b, int64_t P, double chi, const uint64_t* cur, int64_t n, uint64_t* far,
+                             uint64_t* near, uint64_t* next, unsigned long long* cnt, hipStream_t s);
+hipError_t launch_bct_sort_csr(const uint64_t* keys, uint64_t* sorted, int64_t n, void* tmp, size_t tmp_bytes,
+                               int64_t rows, int32_t* off, int32_t* col, hipStream_t s);
 
 // The walk itself: act(node, took) is called on every lane at every node the wave visits,
 // with took = 1 when the node is admissible for the lane, 2 when it is a leaf the lane sums
@@ -63,13 +78,6 @@ __device__ __forceinline__ void wave_walk(const double* __restrict__ na, int64_t
         if (took == 1) far(node);
         else if (took == 2) near(node);
     });
-}
-
-// Sum of v over the 64 lanes of a wave, in a fixed order (every lane gets the sum).
-__device__ __forceinline__ double wave_sum(double v)
-{
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
 }
 
 }  // namespace tp
