@@ -389,6 +389,7 @@ struct tp_problem {
     // geometry version they describe and their block counts
     DevBuf<int32_t> bct_far_off, bct_far_col, bct_near_off, bct_near_col;
     DevBuf<uint64_t> bct_fr0, bct_fr1, bct_fkeys, bct_nkeys, bct_sorted, bct_grow;
+    DevBuf<double> bct_rec;
     DevBuf<char> bct_tmp;
     DevBuf<unsigned long long> bct_cnt;
     HostBuf<unsigned long long> bct_hcnt;
@@ -453,7 +454,7 @@ struct tp_problem {
              bh_order.bytes() + bh_pos.bytes() + bh_counts.bytes() + bh_nm.bytes() + bct_far_off.bytes() +
              bct_far_col.bytes() + bct_near_off.bytes() + bct_near_col.bytes() + bct_yt.bytes() +
              bct_fr0.bytes() + bct_fr1.bytes() + bct_fkeys.bytes() + bct_nkeys.bytes() + bct_sorted.bytes() +
-             bct_grow.bytes() + bct_tmp.bytes() + bct_cnt.bytes();
+             bct_grow.bytes() + bct_tmp.bytes() + bct_cnt.bytes() + bct_rec.bytes();
         b += ng_kin.bytes() + ng_kout.bytes() + ng_vin.bytes() + ng_vout.bytes() + ng_sfx.bytes() + ng_sfl.bytes() +
              ng_cell.bytes() + ng_tmp.bytes() + ng_prm.bytes();
         return b;
@@ -1003,6 +1004,8 @@ tp_status ensure_bct(tp_problem* P)
     const int64_t M = (int64_t)bh_node_count(P->nF, P->prm.leaf_size, &Pl);
     TP_TRY(P->bct_cnt.ensure(3, s));
     TP_TRY(P->bct_hcnt.ensure(3));
+    TP_TRY(P->bct_rec.ensure((size_t)8 * M, s));
+    TP_HIP(launch_bct_nodes(P->bh, M, P->bct_rec.p, s));
     TP_TRY(P->bct_fr0.ensure(1024, s));
     const uint64_t root = (1ull << 32) | 1ull;
     TP_HIP(hipMemcpyAsync(P->bct_fr0.p, &root, sizeof(root), hipMemcpyHostToDevice, s));
@@ -1019,7 +1022,7 @@ tp_status ensure_bct(tp_problem* P)
         h[1] = (unsigned long long)nnear;
         h[2] = 0;
         TP_HIP(hipMemcpyAsync(P->bct_cnt.p, h, 3 * sizeof(unsigned long long), hipMemcpyHostToDevice, s));
-        TP_HIP(launch_bct_expand(P->bh, Pl, P->prm.chi, cur->p, n, P->bct_fkeys.p, P->bct_nkeys.p, nxt->p,
+        TP_HIP(launch_bct_expand(P->bct_rec.p, Pl, P->prm.chi, cur->p, n, P->bct_fkeys.p, P->bct_nkeys.p, nxt->p,
                                  P->bct_cnt.p, s));
         TP_HIP(hipMemcpyAsync(h, P->bct_cnt.p, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         TP_HIP(hipStreamSynchronize(s));

@@ -784,43 +784,110 @@ hipError_t bct_launch(const BhBuffers& b, const BctLists& bl, int64_t nF, int le
 // level's blocks land is arbitrary; the lists are then sorted by (row, column), which fixes
 // them.  The separation test repeats the reading's arithmetic in FP64 without fused
 // multiply-adds, as for the Barnes-Hut admissibility.
-__device__ __forceinline__ bool bct_separated(const double* __restrict__ nlo, const double* __restrict__ nhi,
-                                              const double* __restrict__ nr2, int64_t I, int64_t J, double chi2)
+// Node records for the split: lo (3), hi (3), r^2, a_I -- one 64-byte line per node, since
+// the pairs of a level reach their nodes in no cache-friendly order.
+__global__ void k_bct_nodes(int64_t M, const double* __restrict__ na, const double* __restrict__ nlo,
+                            const double* __restrict__ nhi, const double* __restrict__ nr2, double* __restrict__ rec)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= M) return;
+    double* r = rec + 8 * i;
+    for (int m = 0; m < 3; ++m) {
+        r[m] = nlo[3 * i + m];
+        r[3 + m] = nhi[3 * i + m];
+    }
+    r[6] = nr2[i];
+    r[7] = na[i];
+}
+
+__device__ __forceinline__ bool bct_separated(const double (&a)[8], const double (&b)[8], double chi2)
 {
     double d2 = 0.0;
     for (int m = 0; m < 3; ++m) {
-        const double g1 = nlo[3 * J + m] - nhi[3 * I + m];
-        const double g2 = nlo[3 * I + m] - nhi[3 * J + m];
+        const double g1 = b[m] - a[3 + m];
+        const double g2 = a[m] - b[3 + m];
         double g = g1 > g2 ? g1 : g2;
         g = g < 0.0 ? 0.0 : g;
         d2 = d2 + g * g;
     }
-    const double r2 = nr2[I] > nr2[J] ? nr2[I] : nr2[J];
+    const double r2 = a[6] > b[6] ? a[6] : b[6];
     return r2 < chi2 * d2;
 }
 
+// One level of the split: each thread takes kExpPer pairs; the block counts its appends
+// per list (wave prefix sums, then across the block's waves) and reserves them with one
+// atomic addition per list, so same-address atomics stay few.
 // cnt[0], cnt[1]: admissible and exact blocks so far (appended at these positions);
 // cnt[2]: pairs of the next level.
-__global__ void k_bct_expand(const uint64_t* __restrict__ cur, int64_t n, const double* __restrict__ na,
-                             const double* __restrict__ nlo, const double* __restrict__ nhi,
-                             const double* __restrict__ nr2, int64_t P, double chi2, uint64_t* __restrict__ far,
-                             uint64_t* __restrict__ near, uint64_t* __restrict__ next,
-                             unsigned long long* __restrict__ cnt)
+constexpr int kExpThreads = 1024, kExpPer = 4;
+
+__global__ __launch_bounds__(kExpThreads) void k_bct_expand(const uint64_t* __restrict__ cur, int64_t n,
+                                                            const double4* __restrict__ rec, int64_t P, double chi2,
+                                                            uint64_t* __restrict__ far, uint64_t* __restrict__ near,
+                                                            uint64_t* __restrict__ next,
+                                                            unsigned long long* __restrict__ cnt)
 {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= n) return;
-    const uint64_t key = cur[e];
-    const int64_t I = (int64_t)(key >> 32), J = (int64_t)(key & 0xffffffffull);
-    if (!(na[I] > 0.0) || !(na[J] > 0.0)) return;
-    if (bct_separated(nlo, nhi, nr2, I, J, chi2)) {
-        far[atomicAdd(&cnt[0], 1ull)] = key;
-    } else if (I >= P) {                        // two leaves (pairs stay on one depth)
-        near[atomicAdd(&cnt[1], 1ull)] = ((uint64_t)(I - P) << 32) | (uint64_t)(J - P);
-    } else {
-        const unsigned long long o = atomicAdd(&cnt[2], 4ull);
-        for (int a = 0; a < 2; ++a)
-            for (int c = 0; c < 2; ++c)
-                next[o + 2 * a + c] = ((uint64_t)(2 * I + a) << 32) | (uint64_t)(2 * J + c);
+    __shared__ unsigned long long wsum[3][kExpThreads / 64];
+    __shared__ unsigned long long base[3];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t e0 = (int64_t)blockIdx.x * kExpThreads * kExpPer + tid;
+    uint64_t key[kExpPer];
+    int what[kExpPer];                          // 1 admissible, 2 exact, 3 split, 0 nothing
+    unsigned long long c[3] = {0ull, 0ull, 0ull};
+#pragma unroll
+    for (int q = 0; q < kExpPer; ++q) {
+        const int64_t e = e0 + (int64_t)q * kExpThreads;
+        key[q] = 0;
+        what[q] = 0;
+        if (e < n) {
+            key[q] = cur[e];
+            const int64_t I = (int64_t)(key[q] >> 32), J = (int64_t)(key[q] & 0xffffffffull);
+            const double4 a0 = rec[2 * I], a1 = rec[2 * I + 1], b0 = rec[2 * J], b1 = rec[2 * J + 1];
+            const double av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+            const double bv[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+            if (av[7] > 0.0 && bv[7] > 0.0)
+                what[q] = bct_separated(av, bv, chi2) ? 1 : (I >= P ? 2 : 3);   // pairs stay on one depth
+        }
+        if (what[q]) c[what[q] - 1] += what[q] == 3 ? 4ull : 1ull;
+    }
+    unsigned long long incl[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        unsigned long long v = c[k];
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned long long t = __shfl_up(v, o, 64);
+            if (lane >= o) v += t;
+        }
+        incl[k] = v;
+        if (lane == 63) wsum[k][wid] = v;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        unsigned long long tot = 0ull;
+        for (int w = 0; w < kExpThreads / 64; ++w) {
+            const unsigned long long v = wsum[tid][w];
+            wsum[tid][w] = tot;
+            tot += v;
+        }
+        base[tid] = tot ? atomicAdd(&cnt[tid], tot) : 0ull;
+    }
+    __syncthreads();
+    unsigned long long off[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) off[k] = base[k] + wsum[k][wid] + incl[k] - c[k];
+#pragma unroll
+    for (int q = 0; q < kExpPer; ++q) {
+        const int64_t I = (int64_t)(key[q] >> 32), J = (int64_t)(key[q] & 0xffffffffull);
+        if (what[q] == 1) {
+            far[off[0]++] = key[q];
+        } else if (what[q] == 2) {
+            near[off[1]++] = ((uint64_t)(I - P) << 32) | (uint64_t)(J - P);
+        } else if (what[q] == 3) {
+            for (int a = 0; a < 2; ++a)
+                for (int b = 0; b < 2; ++b)
+                    next[off[2] + 2 * a + b] = ((uint64_t)(2 * I + a) << 32) | (uint64_t)(2 * J + b);
+            off[2] += 4;
+        }
     }
 }
 
@@ -961,12 +1028,20 @@ size_t bct_sort_temp_bytes(int64_t n)
     return bytes;
 }
 
-hipError_t launch_bct_expand(const BhBuffers& b, int64_t P, double chi, const uint64_t* cur, int64_t n, uint64_t* far,
+hipError_t launch_bct_nodes(const BhBuffers& b, int64_t M, double* rec, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bct_nodes, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, M, b.na, b.nlo, b.nhi, b.nr2,
+                       rec);
+    return hipGetLastError();
+}
+
+hipError_t launch_bct_expand(const double* rec, int64_t P, double chi, const uint64_t* cur, int64_t n, uint64_t* far,
                              uint64_t* near, uint64_t* next, unsigned long long* cnt, hipStream_t s)
 {
     if (n < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_bct_expand, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, cur, n, b.na, b.nlo, b.nhi,
-                       b.nr2, P, chi * chi, far, near, next, cnt);
+    const int64_t per_block = (int64_t)kExpThreads * kExpPer;
+    hipLaunchKernelGGL(k_bct_expand, dim3((unsigned)((n + per_block - 1) / per_block)), dim3(kExpThreads), 0, s, cur,
+                       n, reinterpret_cast<const double4*>(rec), P, chi * chi, far, near, next, cnt);
     return hipGetLastError();
 }
 

@@ -25,7 +25,9 @@ namespace tp {
 // n more entries and next for 4n), then launch_bct_sort_csr turns a list into CSR rows
 // (sorted by row and column; off [rows + 1], col [n]).
 size_t bct_sort_temp_bytes(int64_t n);
-hipError_t launch_bct_expand(const BhBuffers& b, int64_t P, double chi, const uint64_t* cur, int64_t n, uint64_t* far,
+// rec [M][8] (64-byte aligned): per node lo, hi, r^2, a_I, written by launch_bct_nodes.
+hipError_t launch_bct_nodes(const BhBuffers& b, int64_t M, double* rec, hipStream_t s);
+hipError_t launch_bct_expand(const double* rec, int64_t P, double chi, const uint64_t* cur, int64_t n, uint64_t* far,
                              uint64_t* near, uint64_t* next, unsigned long long* cnt, hipStream_t s);
 hipError_t launch_bct_sort_csr(const uint64_t* keys, uint64_t* sorted, int64_t n, void* tmp, size_t tmp_bytes,
                                int64_t rows, int32_t* off, int32_t* col, hipStream_t s);
