@@ -362,6 +362,7 @@ __global__ __launch_bounds__(256) void k_bh_traverse(BhArgs A)
                 }
             }
         });
+    wave_count_terms(A.counts, nfar, nnear);
     if (!live) return;
     A.eS[s] = e;
     if (GRAD) {
@@ -371,8 +372,6 @@ __global__ __launch_bounds__(256) void k_bh_traverse(BhArgs A)
         }
         A.gS[6 * A.nF + s] = ga;
     }
-    atomicAdd(&A.counts[0], nfar);
-    atomicAdd(&A.counts[1], nnear);
 }
 
 // Per-face partial derivatives: face side + target side + the node terms of every

@@ -74,7 +74,8 @@ __global__ __launch_bounds__(kBlock) void k_obs_pairs(const double4* __restrict_
 // r_I^2 < theta^2 dist(X_T, box_I)^2 (decided in FP64 without fused multiply-adds, so the
 // interaction lists are a function of the meshes alone) and then contributes
 // a_I |X_I - X_T|^-p; a leaf that is not admissible contributes its faces one by one.  Each
-// thread sums its own terms in traversal order; the term counts are integer atomics.
+// thread sums its own terms in traversal order; the term counts are summed per wave and
+// added with one integer atomic per wave.
 struct ObsTreeArgs {
     const double4* dx;        // surface face data (X_T, a_T)
     int64_t nF;
@@ -143,6 +144,7 @@ __global__ __launch_bounds__(256) void k_obs_bh(ObsTreeArgs A)
                 ++nnear;
             }
         });
+    wave_count_terms(A.counts, nfar, nnear);
     if (!live) return;
     const int64_t gs = A.gs;
     A.e[T] = x.w * phi;
@@ -153,8 +155,6 @@ __global__ __launch_bounds__(256) void k_obs_bh(ObsTreeArgs A)
     A.g[4 * gs + T] = 0.0;
     A.g[5 * gs + T] = 0.0;
     A.g[6 * gs + T] = phi;
-    atomicAdd(&A.counts[0], nfar);
-    atomicAdd(&A.counts[1], nnear);
 }
 
 __global__ void k_implicit(const double4* __restrict__ dx, int64_t nF, ImplicitSet set, double* __restrict__ e,

@@ -72,6 +72,21 @@ __device__ __forceinline__ void wave_walk_act(const double* __restrict__ na, int
     }
 }
 
+// Add this lane's far and near term counts to counts[0], counts[1]: summed across the wave
+// first, one atomic addition per wave.  All lanes of the wave must call this together.
+__device__ __forceinline__ void wave_count_terms(unsigned long long* counts, unsigned long long nfar,
+                                                 unsigned long long nnear)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        nfar += __shfl_xor(nfar, o, 64);
+        nnear += __shfl_xor(nnear, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        if (nfar) atomicAdd(&counts[0], nfar);
+        if (nnear) atomicAdd(&counts[1], nnear);
+    }
+}
+
 template <class Adm, class Far, class Near>
 __device__ __forceinline__ void wave_walk(const double* __restrict__ na, int64_t P, bool live, Adm&& adm, Far&& far,
                                           Near&& near)
