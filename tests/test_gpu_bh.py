@@ -244,3 +244,27 @@ def test_tree_fractional_shapes(tp, leaf, k):
         assert tuple(P.bct_stats()) == cnt
     assert np.linalg.norm(L1 - Lb) <= 1e-12 * np.linalg.norm(Lb)
     assert np.linalg.norm(L2 - Lc) <= 1e-12 * np.linalg.norm(Lc)
+
+
+def test_bh_bumpy_sphere_full_size_vs_oracle(tp):
+    """The 327,680-face bumpy sphere at theta = 0.5 (the precision sweep's Barnes-Hut case),
+    FP64 pair terms: the same far and near term counts as the oracle's Barnes-Hut on the same
+    tree (every admissibility decision equal at full size), E_BH to 1e-12 and dE_BH to 1e-10
+    against the oracle (target-side sums with atomics); the FP32 walk within 1e-5 (E) and
+    1e-4 (dE, the bound used on the linked tori)."""
+    import oracle as O
+    m = mg.workload("bumpy327k")
+    print(f"[bh] bumpy sphere full size nF={m.nF}: oracle Barnes-Hut", flush=True)
+    E0, g0, cnt = O.bh_gradient(m.V, m.F, 0.5)
+    V, F = dev(m.V), dev(m.F, torch.int32)
+    out = {}
+    for prec in (2, 0):
+        with tp.Problem(V, F, tp.default_params(precision=prec, theta=0.5)) as P:
+            E, g = P.gradient()
+            out[prec] = (E, g.cpu().numpy(), P.bh_stats())
+    print(f"  terms {out[2][2]} (oracle {cnt}); E {abs(out[2][0] - E0) / E0:.2e}, dE {rel(out[2][1], g0):.2e}; "
+          f"FP32 E {abs(out[0][0] - E0) / E0:.2e}, dE {rel(out[0][1], g0):.2e}", flush=True)
+    assert tuple(out[2][2]) == cnt and tuple(out[0][2]) == cnt
+    assert abs(out[2][0] - E0) <= 1e-12 * E0
+    assert rel(out[2][1], g0) <= 1e-10
+    assert abs(out[0][0] - E0) <= 1e-5 * E0 and rel(out[0][1], g0) <= 1e-4
