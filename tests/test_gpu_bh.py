@@ -268,3 +268,24 @@ def test_bh_bumpy_sphere_full_size_vs_oracle(tp):
     assert abs(out[2][0] - E0) <= 1e-12 * E0
     assert rel(out[2][1], g0) <= 1e-10
     assert abs(out[0][0] - E0) <= 1e-5 * E0 and rel(out[0][1], g0) <= 1e-4
+
+
+def test_bct_bumpy_sphere_full_size_vs_oracle(tp):
+    """The block cluster tree product at full size on the 327,680-face sphere (chi = 0.5):
+    the same admissible and exact block counts as the oracle's split, L^sigma u (3 columns)
+    to 1e-12 with FP64 pair terms and 1e-5 with FP32 ones against the oracle's
+    block-by-block product."""
+    import oracle as O
+    m = mg.workload("bumpy327k")
+    u = mg.random_columns(m.nV, 3, 1)
+    print(f"[bct] bumpy sphere full size nF={m.nF}: oracle block-by-block product", flush=True)
+    L0, cnt = O.bct_fractional_apply(m.V, m.F, u, 0.5)
+    V, F = dev(m.V), dev(m.F, torch.int32)
+    for prec, tol in ((2, 1e-12), (0, 1e-5)):
+        with tp.Problem(V, F, tp.default_params(precision=prec, chi=0.5)) as P:
+            L1 = P.fractional_apply(dev(u)).cpu().numpy()
+            stats = P.bct_stats()
+        err = rel(L1, L0)
+        print(f"  precision {prec}: blocks {stats} (oracle {cnt}), vs oracle {err:.2e}", flush=True)
+        assert tuple(stats) == cnt
+        assert err <= tol, err
