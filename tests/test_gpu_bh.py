@@ -289,3 +289,21 @@ def test_bct_bumpy_sphere_full_size_vs_oracle(tp):
         print(f"  precision {prec}: blocks {stats} (oracle {cnt}), vs oracle {err:.2e}", flush=True)
         assert tuple(stats) == cnt
         assert err <= tol, err
+
+
+def test_bh_fractional_bumpy_sphere_full_size_vs_oracle(tp):
+    """The Barnes-Hut fractional apply at full size on the 327,680-face sphere (theta = 0.5,
+    3 columns) against the oracle's Barnes-Hut apply on the same tree: 1e-12 with FP64 pair
+    terms, 1e-5 with FP32 ones."""
+    import oracle as O
+    m = mg.workload("bumpy327k")
+    u = mg.random_columns(m.nV, 3, 1)
+    print(f"[bh] fractional apply full size nF={m.nF}: oracle Barnes-Hut", flush=True)
+    L0 = O.bh_fractional_apply(m.V, m.F, u, 0.5)
+    V, F = dev(m.V), dev(m.F, torch.int32)
+    for prec, tol in ((2, 1e-12), (0, 1e-5)):
+        with tp.Problem(V, F, tp.default_params(precision=prec, theta=0.5)) as P:
+            L1 = P.fractional_apply(dev(u)).cpu().numpy()
+        err = rel(L1, L0)
+        print(f"  precision {prec}: vs oracle {err:.2e}", flush=True)
+        assert err <= tol, err
