@@ -951,3 +951,21 @@ def test_step_vertex_pins(tp, meshes, name):
     assert np.abs(dd[pins]).max() == 0.0
     assert rel(V1 - m.V, ref.V - m.V) <= 1e-4
     assert np.array_equal(V1[pins], m.V[pins]) and np.array_equal(V2[pins], m.V[pins])
+
+
+def test_remesh_then_step(tp):
+    """Remeshing between steps (Sec. 6): a stretched noisy sphere is remeshed on the host
+    (tp_remesh) and a new problem created from the result; its step decreases the energy
+    and keeps the area and volume constraints, like a problem of the original mesh."""
+    m = mg.add_noise(mg.icosphere(3), 0.02, 5)
+    V = m.V * np.array([1.0, 1.0, 2.5])
+    L0 = float(np.mean(np.linalg.norm(V[m.F[:, 0]] - V[m.F[:, 1]], axis=1)))
+    Vr, Fr = tp.tp_remesh(V, m.F, L0, iterations=3, rho=0.5)
+    print(f"[parity] remesh then step: {m.nF} -> {len(Fr)} faces", flush=True)
+    assert len(Fr) != m.nF
+    with tp.Problem(dev(Vr), dev(Fr, torch.int32)) as P:
+        reps = [P.step() for _ in range(2)]
+    for r in reps:
+        assert r.E_new < r.E
+        for q in range(2):
+            assert abs(r.phi_after[q]) <= max(1e-9, abs(r.phi_trial[q]))
