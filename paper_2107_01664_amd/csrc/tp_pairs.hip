@@ -17,6 +17,7 @@
 // to the 6th power, and q is small for near pairs on a smooth surface); tiles far from
 // the i-range (tile_is_far) use the high parts alone.
 #include "tp_internal.h"
+#include "tp_tiles.h"
 
 #include <hipcub/hipcub.hpp>
 
@@ -154,18 +155,6 @@ __device__ __forceinline__ bool tile_hits_diag(int64_t j0, int64_t ibase, int is
     return j0 < ibase + ispan && j0 + kTileJ > ibase;
 }
 
-// Box of the i-range [ibase, ibase + ispan) from the tile boxes.
-__device__ __forceinline__ void irange_box(const float4* tbox, int64_t ibase, int ispan, float4& lo, float4& hi)
-{
-    lo = make_float4(INFINITY, INFINITY, INFINITY, 0.f);
-    hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.f);
-    for (int64_t t = ibase / kTileJ; t < (ibase + ispan) / kTileJ; ++t) {
-        const float4 a = tbox[2 * t], b = tbox[2 * t + 1];
-        lo = make_float4(fminf(lo.x, a.x), fminf(lo.y, a.y), fminf(lo.z, a.z), 0.f);
-        hi = make_float4(fmaxf(hi.x, b.x), fmaxf(hi.y, b.y), fmaxf(hi.z, b.z), 0.f);
-    }
-}
-
 // Can a pair of the i-range box and j-tile jt be closer than the near-field radius?  The
 // boxes hold the FP32 barycenters, within rounding of the hi+lo distances, so the test
 // uses a 1 % margin.
@@ -177,28 +166,6 @@ __device__ __forceinline__ bool tile_may_be_near(const float4& ilo, const float4
     const float gy = fmaxf(fmaxf(a.y - ihi.y, ilo.y - b.y), 0.f);
     const float gz = fmaxf(fmaxf(a.z - ihi.z, ilo.z - b.z), 0.f);
     return gx * gx + gy * gy + gz * gz <= 1.01f * rho2;
-}
-
-// Far tiles drop the low parts of the barycenters.  Without them the difference of two
-// barycenters carries an absolute error of at most 2^-24 (|X_S| + |X_T|) per coordinate
-// (the rounding of X to FP32) instead of 2^-24 |X_S - X_T| with them.  When every pair of
-// the i-range box and the j-tile box is at least kFarRatio x the largest coordinate
-// magnitude of the two boxes apart, that error is at most 2 / kFarRatio = 8 times the
-// rounding of the hi/lo difference, on pairs whose terms fall off as |d|^-7 or faster.
-constexpr float kFarRatio = 0.25f;
-
-__device__ __forceinline__ bool tile_is_far(const float4& ilo, const float4& ihi, const float4* tbox, int jt)
-{
-    const float4 a = tbox[2 * jt], b = tbox[2 * jt + 1];
-    const float gx = fmaxf(fmaxf(a.x - ihi.x, ilo.x - b.x), 0.f);
-    const float gy = fmaxf(fmaxf(a.y - ihi.y, ilo.y - b.y), 0.f);
-    const float gz = fmaxf(fmaxf(a.z - ihi.z, ilo.z - b.z), 0.f);
-    const float m = fmaxf(fmaxf(fmaxf(fabsf(a.x), fabsf(b.x)), fmaxf(fabsf(a.y), fabsf(b.y))),
-                          fmaxf(fmaxf(fabsf(a.z), fabsf(b.z)),
-                                fmaxf(fmaxf(fmaxf(fabsf(ilo.x), fabsf(ihi.x)), fmaxf(fabsf(ilo.y), fabsf(ihi.y))),
-                                      fmaxf(fabsf(ilo.z), fabsf(ihi.z)))));
-    const float g2 = gx * gx + gy * gy + gz * gz;
-    return g2 >= (kFarRatio * kFarRatio) * (m * m);   // false for empty boxes (m = inf)
 }
 
 // ------------------------------------------------------------------ per-face accumulators

@@ -27,6 +27,7 @@
 // The diagonal S = T contributes nothing: d = 0 there, so both differences and q vanish;
 // r2 is set to 1 on it to keep the powers finite.
 #include "tp_sobolev.h"
+#include "tp_tiles.h"
 
 #include <algorithm>
 #include <mutex>
@@ -46,6 +47,7 @@ struct SobArgs {
     const void* fn;     // float4 or double4 (N, 0)
     const void* fu;     // [cap][KC] 4-vectors (D u, ubar)
     double* part;       // [n_split][4 KC][irows]
+    const float4* tbox; // per-tile boxes of the FP32 barycenters (far-tile test)
     int64_t irows;
     int n_itiles, tiles_per_split, ntiles_j;
 };
@@ -184,6 +186,8 @@ __global__ __launch_bounds__(kBlock) void k_sob32(SobArgs A, float ms)
 #pragma unroll
         for (int q = 0; q < 4 * KC; ++q) acc[r][q] = 0.0;
     }
+    float4 ilo, ihi;
+    if (HILO) irange_box(A.tbox, ibase, kBlock * NI, ilo, ihi);
     for (int jt = jt0; jt < jt1; ++jt) {
         const int64_t j0 = (int64_t)jt * kTileJ;
         __syncthreads();
@@ -202,6 +206,8 @@ __global__ __launch_bounds__(kBlock) void k_sob32(SobArgs A, float ms)
             for (int q = 0; q < 4 * KC; ++q) c[r][q] = 0.f;
         if (hits_diag(j0, ibase, kBlock * NI))
             sob_tile32<true, NI, KC, HILO, ROWSUM>(s_x, s_l, s_n, s_u, j0, Sh, Sl, Sn, Su, Si, ms, c);
+        else if (HILO && tile_is_far(ilo, ihi, A.tbox, jt))   // far tiles: the high parts suffice
+            sob_tile32<false, NI, KC, false, ROWSUM>(s_x, s_l, s_n, s_u, j0, Sh, Sl, Sn, Su, Si, ms, c);
         else
             sob_tile32<false, NI, KC, HILO, ROWSUM>(s_x, s_l, s_n, s_u, j0, Sh, Sl, Sn, Su, Si, ms, c);
 #pragma unroll
@@ -405,6 +411,7 @@ hipError_t launch_sobolev_diag(const SobolevCall& c, double* dinv, hipStream_t s
     A.fn = fd.fn;
     A.fu = nullptr;
     A.part = c.part;
+    A.tbox = fd.tbox;
     A.irows = pl.irows;
     A.n_itiles = pl.n_itiles;
     A.tiles_per_split = pl.tiles_per_split;
@@ -442,6 +449,7 @@ hipError_t launch_sobolev(const SobolevCall& c, const double* u, int ldu, int kc
     A.fn = f64 ? (const void*)fd.dn : (const void*)fd.fn;
     A.fu = c.fu;
     A.part = c.part;
+    A.tbox = fd.tbox;
     A.irows = pl.irows;
     A.n_itiles = pl.n_itiles;
     A.tiles_per_split = pl.tiles_per_split;
