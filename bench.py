@@ -13,7 +13,8 @@ Prints ONE JSON line (rank 0).  `--gpus N` with N > 1 exits: the path runs on on
 `--copy-probe` instead runs a plain device-to-device copy of known size; its FETCH_SIZE
 and WRITE_SIZE counter readings calibrate those counters for the traffic figure.
 `--pairs-only` runs only the all-pairs launches of the step (E + dE and L^sigma u) and
-prints their timings: a short program for hardware-counter passes.
+prints their timings: a short program for hardware-counter passes (`--pairs-workload`
+picks another workload for it, e.g. bumpy327k).
 """
 from __future__ import annotations
 
@@ -206,6 +207,8 @@ def parse():
                     help="precision and Barnes-Hut sweep (bumpy sphere, linked tori) instead of the step")
     ap.add_argument("--pairs-only", action="store_true",
                     help="time only the all-pairs launches of the step (for counter passes)")
+    ap.add_argument("--pairs-workload", default="torus40k",
+                    help="workload of --pairs-only (a name known to meshgen.workload)")
     ap.add_argument("--large-solve", action="store_true",
                     help="time the preconditioned Poisson solve (9 columns) on a 163,842-vertex sphere, "
                          "the multi-launch path, against plain CG")
@@ -535,7 +538,7 @@ def main():
                                        saturated=a.serve_saturated, lane_order=a.serve_lane_order)), flush=True)
         return
     dev = torch.device("cuda", 0)
-    mesh = mg.workload("torus40k")
+    mesh = mg.workload(a.pairs_workload if a.pairs_only else "torus40k")
     u_np = mg.random_columns(mesh.nV, 3, 1)
     V = torch.from_numpy(mesh.V).to(dev)
     F = torch.from_numpy(mesh.F).to(dev)

@@ -324,7 +324,16 @@ struct tp_problem {
     DevBuf<double4> dx, dn;
     DevBuf<int> flags;
     bool geom_valid = false;     // fd describes V
-    bool cotan_valid = false;    // lap_val describes V
+    bool cotan_valid = false;    // lap_val describes V (or will, once aux_join is reached)
+
+    // The cotan values, the solvers' matrix and the preconditioner's set-up for new vertex
+    // positions can run on a second stream beside the all-pairs work, which does not read
+    // them (start_cotan); until the problem's stream has waited for aux_join (join_aux)
+    // aux_pending is set, and only calls that leave V and those buffers alone may run.
+    hipStream_t aux = nullptr;
+    hipEvent_t aux_fork = nullptr, aux_join = nullptr;
+    bool aux_pending = false;
+    bool setup_used = false;     // a solve needed the set-up since the positions last changed
 
     // topology (built on first use)
     bool have_vf = false, have_lap = false;
@@ -840,23 +849,74 @@ tp_status ensure_lap(tp_problem* P)
     return TP_OK;
 }
 
+// The cotan values of V, the solvers' matrix and the preconditioner's set-up, on stream s
+// (buffers allocated beforehand: this enqueues kernels only).
+tp_status launch_cotan(tp_problem* P, hipStream_t s)
+{
+    TP_HIP(launch_cotan_values(P->V.p, P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->lap_off.p, P->lap_col.p,
+                               P->lap_val.p, s));
+    // the solvers' matrix: the cotan values, with the pin rows appended (Sec. 7.2)
+    const double* sv = P->lap_val.p;
+    if (P->npins > 0) {
+        TP_HIP(launch_pin_values(P->nV, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->pin_mask.p, P->lap_pin.p, s));
+        sv = P->lap_pin.p;
+    }
+    TP_HIP(launch_csr_to_ell(P->nV, P->lap_off.p, P->lap_col.p, sv, P->ell_w, P->ell_col.p, P->ell_val.p, s));
+    if (P->have_pcg) TP_HIP(launch_pcg_setup(P->pcg, P->V.p, P->lap_off.p, sv, s));
+    return TP_OK;
+}
+
+// Makes the problem's stream wait for the set-up started on the second stream.
+tp_status join_aux(tp_problem* P)
+{
+    if (!P->aux_pending) return TP_OK;
+    TP_HIP(hipStreamWaitEvent(P->stream, P->aux_join, 0));
+    P->aux_pending = false;
+    return TP_OK;
+}
+
+// Starts the set-up for the current V on the second stream, after everything enqueued so
+// far on the problem's stream, so that it runs beside the energy, differential and
+// fractional launches that follow; ensure_cotan joins it.  Does nothing before the
+// topology exists, when the set-up is current, or when no second stream can be made.
+tp_status start_cotan(tp_problem* P)
+{
+    if (!P->have_lap || P->cotan_valid) return TP_OK;
+    TP_TRY(join_aux(P));
+    if (P->npins > 0) TP_TRY(P->lap_pin.ensure(std::max<int64_t>(P->nnz, 1), P->stream));
+    if (!P->aux) {
+        hipStream_t a = nullptr;
+        hipEvent_t f = nullptr, j = nullptr;
+        if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+            if (j) (void)hipEventDestroy(j);
+            if (f) (void)hipEventDestroy(f);
+            if (a) (void)hipStreamDestroy(a);
+            (void)hipGetLastError();
+            return TP_OK;   // ensure_cotan does the set-up on the problem's stream
+        }
+        P->aux = a;
+        P->aux_fork = f;
+        P->aux_join = j;
+    }
+    TP_HIP(hipEventRecord(P->aux_fork, P->stream));
+    TP_HIP(hipStreamWaitEvent(P->aux, P->aux_fork, 0));
+    TP_TRY(launch_cotan(P, P->aux));
+    TP_HIP(hipEventRecord(P->aux_join, P->aux));
+    P->aux_pending = true;
+    P->cotan_valid = true;
+    return TP_OK;
+}
+
 tp_status ensure_cotan(tp_problem* P)
 {
     TP_TRY(ensure_lap(P));
+    TP_TRY(join_aux(P));
+    P->setup_used = true;
     if (!P->cotan_valid) {
-        TP_HIP(launch_cotan_values(P->V.p, P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->lap_off.p,
-                                   P->lap_col.p, P->lap_val.p, P->stream));
-        // the solvers' matrix: the cotan values, with the pin rows appended (Sec. 7.2)
-        const double* sv = P->lap_val.p;
-        if (P->npins > 0) {
-            TP_TRY(P->lap_pin.ensure(std::max<int64_t>(P->nnz, 1), P->stream));
-            TP_HIP(launch_pin_values(P->nV, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->pin_mask.p, P->lap_pin.p,
-                                     P->stream));
-            sv = P->lap_pin.p;
-        }
-        TP_HIP(launch_csr_to_ell(P->nV, P->lap_off.p, P->lap_col.p, sv, P->ell_w, P->ell_col.p, P->ell_val.p,
-                                 P->stream));
-        if (P->have_pcg) TP_HIP(launch_pcg_setup(P->pcg, P->V.p, P->lap_off.p, sv, P->stream));
+        if (P->npins > 0) TP_TRY(P->lap_pin.ensure(std::max<int64_t>(P->nnz, 1), P->stream));
+        TP_TRY(launch_cotan(P, P->stream));
         P->cotan_valid = true;
     }
     return TP_OK;
@@ -2228,6 +2288,7 @@ tp_status step_group(std::vector<StepState*>& G)
             const int c0 = 0;
             if (S->o.area_penalty > 0.0) {
                 const double cA = 2.0 * S->o.area_penalty * (area / S->A0 - 1.0) / S->A0;
+                TP_TRY(ensure_cotan(P));
                 TP_HIP(launch_spmm(n, P->lap_off.p, P->lap_col.p, P->lap_val.p, P->V.p, 3, 3, P->Y.p, 3, s));
                 TP_HIP(launch_axpy_block3(n, P->gbuf.p, 3, 1.0, P->Y.p, 3, 1, &cA, &c0, P->gbuf.p, 3, s));
             }
@@ -2243,6 +2304,7 @@ tp_status step_group(std::vector<StepState*>& G)
     for (StepState* S : G) {
         tp_problem* P = S->P;
         const int64_t n = P->nV;
+        TP_TRY(ensure_cotan(P));   // joins the set-up started with the step
         TP_HIP(launch_copy_cols(n, P->gbuf.p, 3, 3, P->R.p, ncol, s));
         int col = 3;
         if (S->o.constrain_area) {
@@ -2577,7 +2639,8 @@ tp_status run_step_batch(tp_problem* const* probs, int n, const tp_step_opts* op
         tp_problem* P = T.P;
         tp_status st = ensure_initial_measures(P);
         if (st == TP_OK) st = ensure_geometry(P);
-        if (st == TP_OK) st = ensure_cotan(P);
+        if (st == TP_OK) st = ensure_lap(P);
+        if (st == TP_OK) st = start_cotan(P);   // beside the energy and differential
         if (st != TP_OK) {
             if (st == TP_E_DEVICE) return st;
             T.st = st;
@@ -2696,10 +2759,14 @@ struct ProblemGuard {
     }
 };
 
-tp_status bind(tp_problem* P)
+// Every entry point on a problem starts here.  Unless join is false (calls that neither
+// write V nor read the cotan values, the solvers' matrix or the preconditioner), the
+// problem's stream first waits for a set-up still running on the second stream.
+tp_status bind(tp_problem* P, bool join = true)
 {
     if (!P) return fail(TP_E_INVALID_ARGUMENT, "problem is NULL");
     TP_HIP(hipSetDevice(P->device));
+    if (join) TP_TRY(join_aux(P));
     return TP_OK;
 }
 
@@ -2807,6 +2874,12 @@ void tp_problem_destroy(tp_problem* prob)
     if (!prob) return;
     (void)hipSetDevice(prob->device);
     (void)hipStreamSynchronize(prob->stream);
+    if (prob->aux) {
+        (void)hipStreamSynchronize(prob->aux);
+        (void)hipEventDestroy(prob->aux_fork);
+        (void)hipEventDestroy(prob->aux_join);
+        (void)hipStreamDestroy(prob->aux);
+    }
     delete prob;
 }
 
@@ -2817,6 +2890,11 @@ tp_status tp_problem_set_vertices(tp_problem* P, const double* V)
     TP_HIP(hipMemcpyAsync(P->V.p, V, sizeof(double) * 3 * P->nV, hipMemcpyDeviceToDevice, P->stream));
     P->geom_valid = false;
     P->cotan_valid = false;
+    // a problem whose last positions were solved with will likely be solved with again:
+    // start the set-up for the new ones beside the work that comes first
+    const bool solved = P->setup_used;
+    P->setup_used = false;
+    if (solved) TP_TRY(start_cotan(P));
     return geometry(P);
 }
 
@@ -2831,7 +2909,7 @@ tp_status tp_problem_get_vertices(tp_problem* P, double* V_out)
 
 tp_status tp_problem_energy(tp_problem* P, double* E_out)
 {
-    TP_TRY(bind(P));
+    TP_TRY(bind(P, false));   // runs beside a pending set-up
     if (!E_out) return fail(TP_E_INVALID_ARGUMENT, "E_out is NULL");
     set_error("");
     TP_TRY(ensure_geometry(P));
@@ -2840,7 +2918,7 @@ tp_status tp_problem_energy(tp_problem* P, double* E_out)
 
 tp_status tp_problem_gradient(tp_problem* P, double* E_out, double* dE_out)
 {
-    TP_TRY(bind(P));
+    TP_TRY(bind(P, false));   // runs beside a pending set-up
     if (!E_out || !dE_out) return fail(TP_E_INVALID_ARGUMENT, "E_out and dE_out must be non-NULL");
     set_error("");
     TP_TRY(ensure_geometry(P));
@@ -2851,7 +2929,7 @@ tp_status tp_problem_gradient(tp_problem* P, double* E_out, double* dE_out)
 
 tp_status tp_problem_fractional_apply(tp_problem* P, const double* u, int k, double* Lu_out)
 {
-    TP_TRY(bind(P));
+    TP_TRY(bind(P, false));   // runs beside a pending set-up
     if (!u || !Lu_out) return fail(TP_E_INVALID_ARGUMENT, "u and Lu_out must be non-NULL");
     if (k < 1 || k > kMaxCols) return fail(TP_E_INVALID_ARGUMENT, "k must lie in [1, 64]");
     set_error("");

@@ -918,6 +918,64 @@ def test_step_warm_start(tp, meshes):
     assert rel(Vw - m.V, Vc - m.V) <= 1e-7
 
 
+@pytest.mark.parametrize("name", ["torus37x23", "linked_small"])
+def test_setup_beside_pair_work(tp, meshes, name):
+    """After a solve, new vertex positions start the cotan values and the preconditioner's
+    set-up on a second stream, beside the energy, differential and fractional launches that
+    follow.  Everything computed then equals bit for bit what a problem of the same face
+    order computes with the set-up done in line: after one change of positions, after two
+    changes in a row (the second waits for the first's set-up before it overwrites the
+    positions), and with pins set while a set-up runs."""
+    m = meshes[name]
+    print(f"[parity] set-up beside the pair work {name}", flush=True)
+    rng = np.random.default_rng(11)
+    V1 = m.V + 2e-3 * rng.standard_normal(m.V.shape)
+    V2 = m.V + 4e-3 * rng.standard_normal(m.V.shape)
+    F = dev(m.F, torch.int32)
+    b = dev(mg.random_columns(m.nV, 3, 4))
+    u = dev(mg.random_columns(m.nV, 3, 5))
+    _, labels = O.components(m.F, m.nV)
+    pins = [int(np.nonzero(labels == 0)[0][7])]
+
+    def run(P):
+        E, g = P.gradient()
+        Lu = P.fractional_apply(u)
+        x, rep = P.precond_apply(b)
+        return E, g.cpu().numpy(), Lu.cpu().numpy(), x.cpu().numpy(), list(rep.cg_iters)
+
+    def in_line(V, with_pins=False):
+        # face order and block partition from m.V, as for the problem below; the first new
+        # positions start a set-up that the second call waits for and discards, so the
+        # set-up for V runs in line, on the problem's stream
+        with tp.Problem(dev(m.V), F) as Q:
+            Q.precond_apply(b)
+            Q.set_vertices(dev(V))
+            Q.set_vertices(dev(V))
+            if with_pins:
+                Q.set_pins(pins)
+            return run(Q)
+
+    def same(got, ref):
+        assert got[0] == ref[0]
+        for a, r in zip(got[1:4], ref[1:4]):
+            assert np.array_equal(a, r)
+        assert got[4] == ref[4]
+
+    ref1, ref2, ref1p = in_line(V1), in_line(V2), in_line(V1, True)
+    with tp.Problem(dev(m.V), F) as P:
+        P.precond_apply(b)
+        P.set_vertices(dev(V1))          # starts the set-up beside the pair work
+        same(run(P), ref1)
+        P.set_vertices(dev(V2))
+        P.set_vertices(dev(V1))          # waits for the set-up of V2 first
+        same(run(P), ref1)
+        P.set_vertices(dev(V2))
+        same(run(P), ref2)
+        P.set_vertices(dev(V1))
+        P.set_pins(pins)                 # waits, then the pinned matrix is set up in line
+        same(run(P), ref1p)
+
+
 @pytest.mark.parametrize("name", ["small_sphere", "linked_small"])
 def test_step_vertex_pins(tp, meshes, name):
     """Vertex pins (Sec. 7.1.2) as rows of the preconditioner's Laplacians (Sec. 7.2): the
