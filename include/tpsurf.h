@@ -196,7 +196,14 @@ TP_API tp_status tp_problem_create(const double* V, int64_t nV, const int32_t* F
                             const tp_params* params, void* stream, tp_problem** out);
 TP_API void      tp_problem_destroy(tp_problem* prob);
 
-/* Replace / read the current vertex positions (device, nV x 3). */
+/* Replace / read the current vertex positions (device, nV x 3).
+ * When the previous positions were used by a Poisson solve, set_vertices also starts the
+ * cotan values, the solvers' matrix and the preconditioner's set-up for the new positions
+ * on a second stream of the problem (default priority), after the work enqueued so far on
+ * the problem's stream; tp_precond_step does the same at its start.  The energy, gradient
+ * and fractional-apply calls run beside it; every other call on the problem first makes
+ * the problem's stream wait for it, and tp_problem_destroy waits for both streams.  Results
+ * are the same bit for bit as with the set-up done on the problem's stream. */
 TP_API tp_status tp_problem_set_vertices(tp_problem* prob, const double* V);
 TP_API tp_status tp_problem_get_vertices(tp_problem* prob, double* V_out);
 
