@@ -42,8 +42,8 @@ PEAK_HBM_GBS = 8000.0
 GRAD_TRAFFIC = {
     "sources": ["paper_2107_01664_amd/csrc/tp_pairs.hip", "paper_2107_01664_amd/csrc/tp_tiles.h",
                 "paper_2107_01664_amd/csrc/tp_internal.h"],
-    "sha256": "b74df50fdcb4945fbf31985efdabd5abf78c60969823d93aaf9485544a136f71",
-    "fetch_bytes": int(55113.65625 * 1024) * 2,
+    "sha256": "5bd7a8862143e8ee7c5789495fd4e7e1c91c7340e3f8af50ad4e9328b11fe77e",
+    "fetch_bytes": int(55042.640625 * 1024) * 2,
     "write_bytes": 64148 * 1024,
 }
 

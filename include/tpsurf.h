@@ -486,7 +486,9 @@ TP_API tp_status tp_set_allocator(tp_alloc_fn alloc, tp_free_fn free_, void* use
  * bracketed by HIP events recorded on the stream it runs on; the elapsed device time,
  * the number of ordered face pairs it covered and the launch count are accumulated per
  * kind: 0 = energy, 1 = energy + differential, 2 = fractional apply, 3 = the inner-product
- * operator A (tp_sobolev_apply; the pair kernel alone).  Process-global. */
+ * operator A (tp_sobolev_apply; the pair kernel alone).  Process-global.  Timing never
+ * makes the host wait: the events are read when tp_profile_get or tp_profile_reset is
+ * called, which wait for the launches still running. */
 typedef struct {
     double  ms_total;      /* summed device time of the launches                        */
     double  pairs_total;   /* summed ordered pairs S != T evaluated (columns not counted) */

@@ -52,17 +52,52 @@ const DeviceInfo& device_info()
 
 // ------------------------------------------------------------------ kernel timing
 
+// Per-launch durations of the all-pairs kernels, from HIP events recorded on the launch
+// stream.  A launch's pair of events is kept pending and resolved only when the figures are
+// read or reset, so that measuring never makes the host wait for the GPU.
 struct Profiler {
+    struct Pending {
+        hipEvent_t a, b;
+        int kind;
+        double pairs, cols;
+    };
     std::mutex mu;
     bool on = false;
     tp_kernel_stats st[4];
+    std::vector<Pending> pending;
+
+    // Adds the finished launches to the figures (all of them, waiting, when wait is set)
+    // and releases their events.  Called with mu held.
+    void resolve(bool wait)
+    {
+        size_t keep = 0;
+        for (size_t i = 0; i < pending.size(); ++i) {
+            Pending& p = pending[i];
+            const hipError_t q = wait ? hipEventSynchronize(p.b) : hipEventQuery(p.b);
+            if (q == hipErrorNotReady) {
+                pending[keep++] = p;
+                continue;
+            }
+            float ms = 0.f;
+            if (q == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+                st[p.kind].ms_total += ms;
+                st[p.kind].pairs_total += p.pairs;
+                st[p.kind].cols_total += p.cols;
+                st[p.kind].launches += 1;
+            }
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        pending.resize(keep);
+        (void)hipGetLastError();
+    }
 };
 constexpr int kKindSobolev = 3;   // profile slot of the inner-product operator's pair kernel
 static Profiler g_prof;
 
 struct PairTimer {
     hipEvent_t a = nullptr, b = nullptr;
-    bool on = false;
+    bool on = false, stopped = false;
     int kind = 0;
     double pairs = 0, cols = 0;
     hipStream_t s = nullptr;
@@ -80,19 +115,15 @@ struct PairTimer {
     void stop()
     {
         if (!on) return;
-        (void)hipEventRecord(b, s);
+        stopped = hipEventRecord(b, s) == hipSuccess;
     }
     ~PairTimer()
     {
-        if (on) {
-            float ms = 0.f;
-            if (hipEventSynchronize(b) == hipSuccess && hipEventElapsedTime(&ms, a, b) == hipSuccess) {
-                std::lock_guard<std::mutex> lk(g_prof.mu);
-                g_prof.st[kind].ms_total += ms;
-                g_prof.st[kind].pairs_total += pairs;
-                g_prof.st[kind].cols_total += cols;
-                g_prof.st[kind].launches += 1;
-            }
+        if (on && stopped) {
+            std::lock_guard<std::mutex> lk(g_prof.mu);
+            g_prof.pending.push_back({a, b, kind, pairs, cols});
+            if (g_prof.pending.size() >= 256) g_prof.resolve(false);
+            return;
         }
         if (a) (void)hipEventDestroy(a);
         if (b) (void)hipEventDestroy(b);
@@ -866,7 +897,29 @@ tp_status launch_cotan(tp_problem* P, hipStream_t s)
     return TP_OK;
 }
 
-// Makes the problem's stream wait for the set-up started on the second stream.
+// The problem's second stream and its two events, made on first use; false if they cannot
+// be made (then everything runs on the problem's stream).
+bool ensure_aux(tp_problem* P)
+{
+    if (P->aux) return true;
+    hipStream_t a = nullptr;
+    hipEvent_t f = nullptr, j = nullptr;
+    if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
+        if (j) (void)hipEventDestroy(j);
+        if (f) (void)hipEventDestroy(f);
+        if (a) (void)hipStreamDestroy(a);
+        (void)hipGetLastError();
+        return false;
+    }
+    P->aux = a;
+    P->aux_fork = f;
+    P->aux_join = j;
+    return true;
+}
+
+// Makes the problem's stream wait for the work started on the second stream.
 tp_status join_aux(tp_problem* P)
 {
     if (!P->aux_pending) return TP_OK;
@@ -884,22 +937,7 @@ tp_status start_cotan(tp_problem* P)
     if (!P->have_lap || P->cotan_valid) return TP_OK;
     TP_TRY(join_aux(P));
     if (P->npins > 0) TP_TRY(P->lap_pin.ensure(std::max<int64_t>(P->nnz, 1), P->stream));
-    if (!P->aux) {
-        hipStream_t a = nullptr;
-        hipEvent_t f = nullptr, j = nullptr;
-        if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess ||
-            hipEventCreateWithFlags(&f, hipEventDisableTiming) != hipSuccess ||
-            hipEventCreateWithFlags(&j, hipEventDisableTiming) != hipSuccess) {
-            if (j) (void)hipEventDestroy(j);
-            if (f) (void)hipEventDestroy(f);
-            if (a) (void)hipStreamDestroy(a);
-            (void)hipGetLastError();
-            return TP_OK;   // ensure_cotan does the set-up on the problem's stream
-        }
-        P->aux = a;
-        P->aux_fork = f;
-        P->aux_join = j;
-    }
+    if (!ensure_aux(P)) return TP_OK;   // ensure_cotan does the set-up on the problem's stream
     TP_HIP(hipEventRecord(P->aux_fork, P->stream));
     TP_HIP(hipStreamWaitEvent(P->aux, P->aux_fork, 0));
     TP_TRY(launch_cotan(P, P->aux));
@@ -1649,6 +1687,7 @@ tp_status run_sobolev(tp_problem* P, const double* u, int ldu, int k, double* Au
         const double pairs = (double)P->nF * (double)(P->nF - 1);
         PairTimer t(kKindSobolev, pairs, pairs * kc, s);
         TP_HIP(launch_sobolev(c, u, ldu, kc, Au, ldo, c0, t.on ? t.a : nullptr, t.on ? t.b : nullptr, s));
+        t.stopped = t.on;   // launch_sobolev recorded both events around the pair kernel
     }
     return TP_OK;
 }
@@ -3413,6 +3452,7 @@ tp_status tp_set_allocator(tp_alloc_fn alloc, tp_free_fn free_, void* user)
 tp_status tp_profile_reset(void)
 {
     std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.resolve(true);
     for (auto& s : g_prof.st) std::memset(&s, 0, sizeof(s));
     return TP_OK;
 }
@@ -3421,6 +3461,7 @@ tp_status tp_profile_get(int kind, tp_kernel_stats* out)
 {
     if (kind < 0 || kind > 3 || !out) return TP_E_INVALID_ARGUMENT;
     std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.resolve(true);
     *out = g_prof.st[kind];
     return TP_OK;
 }

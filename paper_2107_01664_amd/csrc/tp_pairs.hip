@@ -788,7 +788,10 @@ __device__ __forceinline__ void kg64(double q, double r2, double inv, double alp
     }
 }
 
-constexpr int kNearBlock = 128;    // faces S per near-field workgroup
+constexpr int kNearBlock = 128;    // threads per near-field workgroup
+constexpr int kNearLanes = 8;      // lanes that share the candidates of one face S
+constexpr int kNearFaces = kNearBlock / kNearLanes;   // faces S per workgroup
+static_assert(kNearBlock % kNearLanes == 0 && 64 % kNearLanes == 0, "a face's lanes lie in one wave");
 
 // Cell of an FP32 barycenter: floor((x - lo) inv_cs) per axis, clamped to [0, g).
 __device__ __forceinline__ int near_cell_axis(float x, float lo, float inv_cs, int g)
@@ -797,18 +800,30 @@ __device__ __forceinline__ int near_cell_axis(float x, float lo, float inv_cs, i
     return c < 0 ? 0 : (c >= g ? g - 1 : c);
 }
 
-// Workgroup = kNearBlock consecutive faces of the cell order (lanes of a wave share cells,
-// so their candidate loops run nearly in step).  Face S visits the 27 cells around its own
-// in a fixed order and, in each, the faces in cell order: for every candidate T it forms the
-// FP32 hi+lo squared distance exactly as the FP32 kernels do, and evaluates the pair in
-// FP64 when that distance is below rho2.  The sums of S therefore have a fixed order.
+// Sum over the kNearLanes lanes of a face by an xor butterfly: every lane ends with the
+// same bits (for four lanes (v0 + v1) + (v2 + v3)), whatever the order the lanes ran in.
+__device__ __forceinline__ double near_lane_sum(double v)
+{
+#pragma unroll
+    for (int o = 1; o < kNearLanes; o <<= 1) v += __shfl_xor(v, o, kNearLanes);
+    return v;
+}
+
+// A workgroup takes kNearFaces consecutive faces of the cell order (faces of a wave share
+// cells, so their candidate loops run nearly in step), kNearLanes lanes per face.  Face S
+// visits the 27 cells around its own in a fixed order and, in each, the faces in cell
+// order; lane l of S takes every kNearLanes-th of them from the l-th on.  For every
+// candidate T the lane forms the FP32 hi+lo squared distance exactly as the FP32 kernels
+// do, and evaluates the pair in FP64 when that distance is below rho2.  Each lane's sums
+// have a fixed order, and so has their combination (near_lane_sum).
 template <bool GEN, bool GRAD>
 __global__ __launch_bounds__(kNearBlock) void k_near64(PairBatch jb, double alpha, double beta)
 {
     const PairJob J = pick_job(jb);
     const NearGridParams G = *J.ngp;
-    const int i = ((int)blockIdx.x - J.block0) * kNearBlock + (int)threadIdx.x;
-    if (i >= G.n) return;
+    const int lane = (int)threadIdx.x % kNearLanes;
+    const int i = ((int)blockIdx.x - J.block0) * kNearFaces + (int)threadIdx.x / kNearLanes;
+    if (i >= G.n) return;   // all lanes of a face leave together
     const int S = J.nord[i];
     const float4 sh = J.nfx[i], sl = J.nfl[i];
     const double4 X = J.dx[S], Nn = J.dn[S];
@@ -823,7 +838,7 @@ __global__ __launch_bounds__(kNearBlock) void k_near64(PairBatch jb, double alph
         for (int y = max(cy - 1, 0); y <= min(cy + 1, G.g - 1); ++y)
             for (int x = max(cx - 1, 0); x <= min(cx + 1, G.g - 1); ++x) {
                 const int2 be = J.ncell[((int64_t)z * G.g + y) * G.g + x];
-                for (int j = be.x; j < be.y; ++j) {
+                for (int j = be.x + lane; j < be.y; j += kNearLanes) {
                     const float4 th = J.nfx[j], tl = J.nfl[j];
                     const float fdx = (sh.x - th.x) + (sl.x - tl.x);
                     const float fdy = (sh.y - th.y) + (sl.y - tl.y);
@@ -860,9 +875,13 @@ __global__ __launch_bounds__(kNearBlock) void k_near64(PairBatch jb, double alph
                 }
             }
     if (!GRAD) {
-        J.part[S] = e;
+        e = near_lane_sum(e);
+        if (lane == 0) J.part[S] = e;
         return;
     }
+#pragma unroll
+    for (int m = 0; m < 11; ++m) c[m] = near_lane_sum(c[m]);
+    if (lane != 0) return;
     const double aS = X.w;
     double o[7];
     o[0] = aS * (alpha * (Nn.x * c[0] + c[1]) - beta * c[4]);
@@ -1260,7 +1279,7 @@ static hipError_t launch_frac_k(const PairJob* jobs, int njobs, int precision, d
     });
 }
 
-int near_block_faces() { return kNearBlock; }
+int near_block_faces() { return kNearFaces; }
 
 int near_grid_gmax(int64_t nF)
 {

@@ -1027,3 +1027,36 @@ def test_remesh_then_step(tp):
         assert r.E_new < r.E
         for q in range(2):
             assert abs(r.phi_after[q]) <= max(1e-9, abs(r.phi_trial[q]))
+
+
+def test_profile_counts_every_kind(tp, meshes):
+    """The launch timing of the four all-pairs kinds: each profiled call adds one launch,
+    its ordered pairs and a positive device time; nothing is counted while disabled, and
+    reset clears the figures."""
+    m = meshes["torus37x23"]
+    print("[parity] profile counts", flush=True)
+    nF = m.nF
+    u = dev(mg.random_columns(m.nV, 3, 1))
+    with tp.Problem(dev(m.V), dev(m.F, torch.int32)) as P:
+        def calls():
+            P.energy()
+            P.gradient()
+            P.fractional_apply(u)
+            P.sobolev_apply(u)
+        calls()
+        torch.cuda.synchronize()
+        tp.profile_reset()
+        tp.profile_enable(True)
+        calls()
+        calls()
+        tp.profile_enable(False)
+        calls()
+        for kind in (tp.KIND_ENERGY, tp.KIND_GRAD, tp.KIND_FRAC, tp.KIND_SOBOLEV):
+            st = tp.profile_get(kind)
+            assert st["launches"] == 2, (kind, st)
+            assert st["pairs_total"] == 2.0 * nF * (nF - 1), (kind, st)
+            assert st["ms_total"] > 0.0, (kind, st)
+            cols = 3.0 if kind in (tp.KIND_FRAC, tp.KIND_SOBOLEV) else 0.0
+            assert st["cols_total"] == cols * st["pairs_total"], (kind, st)
+        tp.profile_reset()
+        assert all(tp.profile_get(k)["launches"] == 0 for k in range(4))
