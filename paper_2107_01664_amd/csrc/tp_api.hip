@@ -58,16 +58,21 @@ const DeviceInfo& device_info()
 struct Profiler {
     struct Pending {
         hipEvent_t a, b;
-        int kind;
+        int device, kind;
         double pairs, cols;
+    };
+    struct Spare {
+        hipEvent_t a, b;
+        int device;
     };
     std::mutex mu;
     bool on = false;
     tp_kernel_stats st[4];
     std::vector<Pending> pending;
+    std::vector<Spare> spare;   // resolved pairs of events, for reuse on their device
 
     // Adds the finished launches to the figures (all of them, waiting, when wait is set)
-    // and releases their events.  Called with mu held.
+    // and keeps their events for reuse.  Called with mu held.
     void resolve(bool wait)
     {
         size_t keep = 0;
@@ -85,8 +90,12 @@ struct Profiler {
                 st[p.kind].cols_total += p.cols;
                 st[p.kind].launches += 1;
             }
-            (void)hipEventDestroy(p.a);
-            (void)hipEventDestroy(p.b);
+            if (spare.size() < 1024) {
+                spare.push_back({p.a, p.b, p.device});
+            } else {
+                (void)hipEventDestroy(p.a);
+                (void)hipEventDestroy(p.b);
+            }
         }
         pending.resize(keep);
         (void)hipGetLastError();
@@ -98,17 +107,25 @@ static Profiler g_prof;
 struct PairTimer {
     hipEvent_t a = nullptr, b = nullptr;
     bool on = false, stopped = false;
-    int kind = 0;
+    int device = 0, kind = 0;
     double pairs = 0, cols = 0;
     hipStream_t s = nullptr;
     PairTimer(int kind_, double pairs_, double cols_, hipStream_t s_) : kind(kind_), pairs(pairs_), cols(cols_), s(s_)
     {
         {
             std::lock_guard<std::mutex> lk(g_prof.mu);
-            on = g_prof.on;
+            on = g_prof.on && hipGetDevice(&device) == hipSuccess;
+            for (size_t i = g_prof.spare.size(); on && i-- > 0;)
+                if (g_prof.spare[i].device == device) {
+                    a = g_prof.spare[i].a;
+                    b = g_prof.spare[i].b;
+                    g_prof.spare[i] = g_prof.spare.back();
+                    g_prof.spare.pop_back();
+                    break;
+                }
         }
         if (on) {
-            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) on = false;
+            if (!a && (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)) on = false;
             else (void)hipEventRecord(a, s);
         }
     }
@@ -121,7 +138,7 @@ struct PairTimer {
     {
         if (on && stopped) {
             std::lock_guard<std::mutex> lk(g_prof.mu);
-            g_prof.pending.push_back({a, b, kind, pairs, cols});
+            g_prof.pending.push_back({a, b, device, kind, pairs, cols});
             if (g_prof.pending.size() >= 256) g_prof.resolve(false);
             return;
         }
