@@ -16,8 +16,9 @@
 // w = C u, the sums gamma = (r,u) and delta = (w,u) give beta = gamma / gamma_old and
 // alpha = gamma / (delta - beta gamma / alpha_old), and p = u + beta p, s = w + beta s (= C p),
 // x += alpha p, r -= alpha s.  One workgroup of 2 kBS threads owns one block (kBS row
-// owners and kBS helpers for the block product) and keeps C_BB^{-1} in LDS for the whole
-// solve.  An iteration has two grid exchanges through per-workgroup flag lines, the
+// owners and kBS helpers for the block product) and keeps C_BB^{-1} for the whole solve: in
+// LDS, or with four or more columns in registers, half a column per thread.  An iteration
+// has two grid exchanges through per-workgroup flag lines, the
 // exchanged values written and read as agent-scope atomics.  In the first, every block
 // publishes its block solve v = C_BB^{-1} r_B and its shares Phi_B^T r of the coarse
 // right-hand side; after it, every workgroup forms the coarse values of the aggregates its
@@ -557,12 +558,20 @@ struct PcgArgs {
 
 constexpr int kCrowMax = 7680;      // cached coarse-inverse entries (FP32: 30 KB)
 
+// With four or more columns a thread keeps its half column of the block inverse in
+// registers; with fewer the inverse stays in LDS (the same product, bit for bit: measured on
+// the 40,000-face torus, registers took 5 % off a 9-column solve, 3 % off a 6-column one,
+// and were no faster with 3).
+template <int KG>
+constexpr bool kRegInv = KG >= 4;
+
 template <int KG>
 struct PcgShared {
-    float Binv[kBS * kBS];
-    float crow[kCrowMax];           // rows of C0inv of the coarse functions of the touching
-                                    // aggregates, rounded to FP32 (as the block inverses are)
-    float r[kBS * KG];              // the vector of the block product, rounded to FP32
+    alignas(16) float Binv[kRegInv<KG> ? 4 : kBS * kBS];
+    alignas(16) float crow[kCrowMax];   // rows of C0inv of the coarse functions of the touching
+                                        // aggregates, rounded to FP32 (as the block inverses are)
+    alignas(16) float r[kBS * KG];      // the vector of the block product, rounded to FP32
+                                        // (16-byte aligned: read four values at a time)
     double rho[kCoarseMax * KG];    // coarse right-hand side [nc][KG] (and the block product's halves)
     double c[kMaxAggNbn * 4 * KG];  // coarse values [slot][4][KG]
     double wave[(kThreads / 64) * 4 * KG];
@@ -679,7 +688,15 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
     const bool act = t < cnt;
     const int64_t i = s0 + t;
 
-    {
+    // Thread t takes half of column tt of C_BB^{-1}: rows jbeg .. jbeg + kBS / 2 (the inverse
+    // is symmetric, so these are row tt's entries), in registers or in LDS for the solve.
+    const int tt = t & (kBS - 1), jbeg = (t / kBS) * (kBS / 2);
+    float binv[kRegInv<KG> ? kBS / 2 : 1];
+    if constexpr (kRegInv<KG>) {
+        const float* src = A.Binv + (int64_t)B * kBS * kBS + tt;
+#pragma unroll
+        for (int q = 0; q < kBS / 2; ++q) binv[q] = src[(int64_t)(jbeg + q) * kBS];
+    } else {
         const float4* src = reinterpret_cast<const float4*>(A.Binv + (int64_t)B * kBS * kBS);
         float4* dst = reinterpret_cast<float4*>(S.Binv);
         for (int q = t; q < kBS * kBS / 4; q += kThreads) dst[q] = src[q];
@@ -790,19 +807,32 @@ __global__ __launch_bounds__(kThreads) void k_pcg(const PcgArgs* __restrict__ ta
         float v32[KG];
 #pragma unroll
         for (int c = 0; c < KG; ++c) v32[c] = 0.0f;
-        const int tt = t & (kBS - 1), jbeg = (t / kBS) * (kBS / 2);
-        constexpr int CH = KG <= 3 ? 8 : (KG <= 6 ? 4 : 2);
+        if constexpr (kRegInv<KG>) {
+            constexpr int CH = KG <= 6 ? 8 : 4;
+#pragma unroll
+            for (int q0 = 0; q0 < kBS / 2; q0 += CH) {
+                float yj[CH * KG];
+#pragma unroll
+                for (int q = 0; q < CH * KG; ++q) yj[q] = S.r[(jbeg + q0) * KG + q];
+#pragma unroll
+                for (int q = 0; q < CH; ++q)
+#pragma unroll
+                    for (int c = 0; c < KG; ++c) v32[c] = __builtin_fmaf(binv[q0 + q], yj[q * KG + c], v32[c]);
+            }
+        } else {
+            constexpr int CH = 8;
 #pragma unroll 1
-        for (int j0 = jbeg; j0 < jbeg + kBS / 2; j0 += CH) {
-            float bj[CH], yj[CH * KG];
+            for (int j0 = jbeg; j0 < jbeg + kBS / 2; j0 += CH) {
+                float bj[CH], yj[CH * KG];
 #pragma unroll
-            for (int q = 0; q < CH; ++q) bj[q] = S.Binv[(j0 + q) * kBS + tt];
+                for (int q = 0; q < CH; ++q) bj[q] = S.Binv[(j0 + q) * kBS + tt];
 #pragma unroll
-            for (int q = 0; q < CH * KG; ++q) yj[q] = S.r[j0 * KG + q];
+                for (int q = 0; q < CH * KG; ++q) yj[q] = S.r[j0 * KG + q];
 #pragma unroll
-            for (int q = 0; q < CH; ++q)
+                for (int q = 0; q < CH; ++q)
 #pragma unroll
-                for (int c = 0; c < KG; ++c) v32[c] = __builtin_fmaf(bj[q], yj[q * KG + c], v32[c]);
+                    for (int c = 0; c < KG; ++c) v32[c] = __builtin_fmaf(bj[q], yj[q * KG + c], v32[c]);
+            }
         }
         // the helpers' halves go through S.rho, which is free until the block sums arrive
         if (t >= kBS) {
