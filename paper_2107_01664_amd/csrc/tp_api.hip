@@ -435,6 +435,7 @@ struct tp_problem {
     double obs_p = 6.0, obs_w = 0.0;
     ObsTree obs_tree;               // Barnes-Hut tree of the obstacle (theta > 0)
     DevBuf<char> ub;
+    DevBuf<float> symp;             // partial sums of the symmetric fractional apply
     DevBuf<double> cg_Z, cg_p, cg_red, cg_relres;
     DevBuf<unsigned> cg_bar;
     DevBuf<int> cg_iters;
@@ -500,7 +501,7 @@ struct tp_problem {
         b += ml_r.bytes() + ml_p.bytes() + ml_s.bytes() + ml_m.bytes() + ml_an.bytes() + ml_v.bytes() +
              ml_shares.bytes() + ml_g.bytes() + ml_part.bytes() + ml_state.bytes();
         b += part.bytes() + gface.bytes() + zbuf.bytes() + scal.bytes() + red.bytes() + vol6.bytes() +
-             edge.bytes() + ub.bytes();
+             edge.bytes() + ub.bytes() + symp.bytes();
         b += cg_Z.bytes() + cg_p.bytes() + cg_red.bytes() + cg_relres.bytes() + cg_bar.bytes() +
              cg_iters.bytes();
         b += R.bytes() + Y.bytes() + W1.bytes() + W2.bytes() + gbuf.bytes() + dir.bytes() + Vt.bytes() +
@@ -562,6 +563,7 @@ tp_status validate_params(const tp_params* in, tp_params& out, double& sigma)
     if (!(out.theta >= 0.0) || !std::isfinite(out.theta)) return fail(TP_E_INVALID_ARGUMENT, "theta must be finite and >= 0");
     if (out.leaf_size < 1 || out.leaf_size > 64) return fail(TP_E_INVALID_ARGUMENT, "leaf_size must lie in [1, 64]");
     if (!(out.chi >= 0.0) || !std::isfinite(out.chi)) return fail(TP_E_INVALID_ARGUMENT, "chi must be finite and >= 0");
+    if (out.frac_sym < -1 || out.frac_sym > 1) return fail(TP_E_INVALID_ARGUMENT, "frac_sym must be -1, 0 or 1");
     sigma = out.sigma;
     if (sigma < 0.0) {
         const double s = (out.beta - 2.0) / out.alpha;   // s = 2 - 2/p when beta = 2 alpha
@@ -1345,6 +1347,21 @@ tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
     return TP_OK;
 }
 
+// The symmetric fractional apply (launch_frac_sym) is used for the direct FP32 sums when its
+// partial buffer stays within kSymPartBytes, and, unless forced by tp_params.frac_sym = 1,
+// from kSymMinFaces faces on, below which it has too few pairs of blocks to fill the GPU.
+constexpr double kSymPartBytes = 256.0 * 1024.0 * 1024.0;
+constexpr int64_t kSymMinFaces = 16384;
+
+bool frac_sym_eligible(const tp_params& prm, int64_t nF, int kc)
+{
+    if (prm.frac_sym == 0 || prm.precision == TP_PREC_FP64 || prm.theta > 0.0 || prm.chi > 0.0 || kc < 1 ||
+        kc > kMaxGroupCols || nF < 1)
+        return false;
+    if (4.0 * (double)frac_sym_part_floats(nF, kc) > kSymPartBytes) return false;
+    return prm.frac_sym == 1 || nF >= kSymMinFaces;
+}
+
 // Lu[m][:, c] = (L^sigma u[m])[:, c] for k columns (row strides ldu, ldl).
 tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, int k, double* const* Lu,
                              int ldl)
@@ -1361,6 +1378,7 @@ tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, in
         const int kp = (kc + 3) / 4 * 4;
         double pairs = 0;
         std::vector<PairJob> direct;
+        std::vector<char> sym(B.size(), 0);
         for (size_t m = 0; m < B.size(); ++m) {
             tp_problem* P = B[m];
             const PairPlan pl = plan_for(kKindFrac, prec, kc, P->nF, P->cap);
@@ -1388,6 +1406,11 @@ tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, in
                                       kc, P->bh_nm.p, P->zbuf.p, pl.irows, s));
                 continue;
             }
+            if (frac_sym_eligible(P->prm, P->nF, kc)) {
+                TP_TRY(P->symp.ensure(frac_sym_part_floats(P->nF, kc), s));
+                sym[m] = 1;
+                continue;
+            }
             TP_TRY(P->part.ensure((size_t)pl.n_split * kc * pl.irows, s));
             jobs[m] = make_pair_job(P->fd, pl, P->part.p, P->ub.p);
             direct.push_back(jobs[m]);
@@ -1399,9 +1422,19 @@ tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, in
             t.stop();
         }
         for (size_t m = 0; m < B.size(); ++m) {
+            if (!sym[m]) continue;
+            tp_problem* P = B[m];
+            const double pp = (double)P->nF * (double)(P->nF - 1);
+            PairTimer t(kKindFrac, pp, pp * kc, s);
+            TP_HIP(launch_frac_sym(P->fd, reinterpret_cast<const float*>(P->ub.p), P->symp.p, prec, P->sigma, kc, s));
+            t.stop();
+        }
+        for (size_t m = 0; m < B.size(); ++m) {
             tp_problem* P = B[m];
             const PairPlan& pl = plans[m];
-            if (!(P->prm.theta > 0.0) && !(P->prm.chi > 0.0))
+            if (sym[m])
+                TP_HIP(launch_reduce_sym(P->symp.p, P->nF, kc, P->zbuf.p, pl.irows, s));
+            else if (!(P->prm.theta > 0.0) && !(P->prm.chi > 0.0))
                 TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, kc, pl.irows, P->nF, P->zbuf.p, pl.irows, s));
             TP_HIP(launch_ut_gather(P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->fd, P->zbuf.p, pl.irows,
                                     kc, ldl, c0, Lu[m], s));
@@ -2792,6 +2825,7 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
     const double gface = std::max((double)pe.irows, 7.0 * pg.irows);
     const double esz = prec == TP_PREC_FP64 ? 8 : 4;
     b += 8 * part + 8 * gface + 8.0 * kf * pf.irows + (double)cap * ((kf + 3) / 4 * 4) * esz;
+    if (frac_sym_eligible(prm, nF, kf)) b += 4.0 * (double)frac_sym_part_floats(nF, kf);
     // step work arrays, per-face volumes and edge lengths, CG tables
     b += 8 * n * ncol * 4 + 8 * n * 3 * 3 + 16 * f + 4096;
     // Barnes-Hut tree, keys, sort scratch and per-face sums (allocated at creation, where
@@ -2891,6 +2925,7 @@ tp_status tp_params_default(tp_params* p)
     p->theta = 0.0;
     p->leaf_size = 8;
     p->chi = 0.0;
+    p->frac_sym = -1;
     return TP_OK;
 }
 

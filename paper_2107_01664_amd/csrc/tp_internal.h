@@ -141,6 +141,26 @@ hipError_t launch_pairs_frac(const PairJob* jobs, int njobs, int precision, doub
 PairPlan plan_for(int kind, int precision, int k, int64_t nF, int64_t cap);
 
 // Sum the n_split partials of every accumulator in split order: out[acc][i].
+// Symmetric all-pairs fractional apply (each unordered pair once, both rows; FP32 pair
+// terms): face data, face-averaged columns ub ([cap][kp] FP32, kp = kc rounded up to 4),
+// tile boxes and an FP32 partial buffer of frac_sym_part_floats(nF, kc) entries.
+struct SymFracArgs {
+    const float4* fx = nullptr;
+    const float4* fl = nullptr;
+    const float* ub = nullptr;
+    const float4* tbox = nullptr;
+    float* part = nullptr;    // [nB][kc][ldp]
+    int64_t ldp = 0;          // nB * frac_sym_block_faces()
+    int nB = 0;               // blocks of frac_sym_block_faces() faces holding the real faces
+};
+int frac_sym_block_faces();
+size_t frac_sym_part_floats(int64_t nF, int kc);
+// The pair kernel (kc = 1..9 columns; precision as for the row-owned kernel, not
+// TP_PREC_FP64), then the sums over the slices: out[c * out_stride + i] for i < nF.
+hipError_t launch_frac_sym(const FaceData& fd, const float* ub, float* part, int precision, double sigma, int kc,
+                           hipStream_t s);
+hipError_t launch_reduce_sym(const float* part, int64_t nF, int kc, double* out, int64_t out_stride, hipStream_t s);
+
 hipError_t launch_reduce_splits(const double* part, int n_split, int nacc, int64_t irows,
                                 int64_t n, double* out, int64_t out_stride, hipStream_t s);
 

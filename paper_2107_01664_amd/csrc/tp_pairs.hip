@@ -576,6 +576,178 @@ __global__ __launch_bounds__(kBlock) void k_frac32(PairBatch jb, float expo)
             part[((int64_t)bs * KC + cc) * irows + Si[r]] = acc[r][cc];
 }
 
+// ============================================================== symmetric fractional apply (FP32)
+//
+// The kernel matrix of L^sigma is symmetric up to the areas: the (T,S) term of row T is
+// g a_S (u_T - u_S) with the same g = r2^expo as the (S,T) term g a_T (u_S - u_T) of row S
+// (and the FP32 difference X_T - X_S is exactly the negated X_S - X_T, so g is the same
+// bits).  Here every unordered pair is evaluated once and adds to both rows.  Faces are
+// cut into blocks of kSymFaces; a wave takes one pair of blocks (a, b), b >= a: its 64
+// lanes hold the kSymNI faces S of block a each, and the faces T of block b pass along the
+// wave 64 at a time, one lane a step (a full-wave DPP rotation), carrying their own column
+// sums.  For b > a both rows collect; the diagonal blocks (b = a) are summed row by row
+// (S-side only, S = T left out), as in k_frac32.  A wave writes its S-side sums to slice b
+// and its T-side sums to slice a of an FP32 partial buffer [nB][kc][ldp]: every face gets
+// each slice exactly once (slices >= its block from its own rows, slices < its block from
+// the waves in which it was T), and k_reduce_sym adds them in slice order in FP64.
+
+constexpr int kSymNI = 4;                 // faces S per lane
+constexpr int kSymFaces = 64 * kSymNI;    // faces per block: one wave's faces S
+
+// Value of the lane one below (lane 0 takes lane 63's): a rotation of the whole wave.
+__device__ __forceinline__ float wave_rotate(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x13C, 0xF, 0xF, false));
+}
+__device__ __forceinline__ int wave_rotate(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false);
+}
+
+template <int KC, bool LO, bool DIAG>
+__device__ __forceinline__ void sym_unit(const SymFracArgs& A, int a, int b, int lane, float expo,
+                                         const float3 (&Sh)[kSymNI], const float3 (&Sl)[kSymNI],
+                                         const float (&aS)[kSymNI], const float (&Su)[kSymNI][KC],
+                                         float (&sacc)[kSymNI][KC])
+{
+    constexpr int KP = KPad<KC>::value;
+    const float* __restrict__ ub = A.ub;
+    for (int q = 0; q < kSymFaces / 64; ++q) {
+        const int64_t T = (int64_t)b * kSymFaces + q * 64 + lane;
+        float4 th = A.fx[T];
+        float3 tl = make_float3(0.f, 0.f, 0.f);
+        if (LO) {
+            const float4 l = A.fl[T];
+            tl = make_float3(l.x, l.y, l.z);
+        }
+        float tu[KC], tacc[KC];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            tu[c] = ub[T * KP + c];
+            tacc[c] = 0.f;
+        }
+        int ti = (int)T;
+#pragma unroll 2
+        for (int step = 0; step < 64; ++step) {
+#pragma unroll
+            for (int r = 0; r < kSymNI; ++r) {
+                float dx, dy, dz;
+                if (LO) {
+                    dx = (Sh[r].x - th.x) + (Sl[r].x - tl.x);
+                    dy = (Sh[r].y - th.y) + (Sl[r].y - tl.y);
+                    dz = (Sh[r].z - th.z) + (Sl[r].z - tl.z);
+                } else {
+                    dx = Sh[r].x - th.x;
+                    dy = Sh[r].y - th.y;
+                    dz = Sh[r].z - th.z;
+                }
+                float r2 = dx * dx + dy * dy + dz * dz;
+                if (DIAG) r2 = ((int)((int64_t)a * kSymFaces + r * 64 + lane) == ti) ? 1.0f : r2;
+                const float g = exp2_fast(expo * log2_fast(r2));
+                const float gaT = g * th.w;
+                const float gaS = g * aS[r];
+#pragma unroll
+                for (int c = 0; c < KC; ++c) {
+                    const float diff = Su[r][c] - tu[c];
+                    sacc[r][c] += gaT * diff;
+                    if (!DIAG) tacc[c] -= gaS * diff;
+                }
+            }
+            th.x = wave_rotate(th.x);
+            th.y = wave_rotate(th.y);
+            th.z = wave_rotate(th.z);
+            th.w = wave_rotate(th.w);
+            if (LO) {
+                tl.x = wave_rotate(tl.x);
+                tl.y = wave_rotate(tl.y);
+                tl.z = wave_rotate(tl.z);
+            }
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                tu[c] = wave_rotate(tu[c]);
+                if (!DIAG) tacc[c] = wave_rotate(tacc[c]);
+            }
+            if (DIAG) ti = wave_rotate(ti);
+        }
+        // 64 rotations later every face T is back in its own lane
+        if (!DIAG) {
+#pragma unroll
+            for (int c = 0; c < KC; ++c) A.part[((int64_t)a * KC + c) * A.ldp + T] = tacc[c];
+        }
+    }
+}
+
+template <int KC, bool HILO>
+__global__ __launch_bounds__(kBlock) void k_frac32_sym(SymFracArgs A, float expo)
+{
+    constexpr int KP = KPad<KC>::value;
+    const int lane = (int)threadIdx.x & 63;
+    const int64_t unit = (int64_t)blockIdx.x * (kBlock / 64) + ((int)threadIdx.x >> 6);
+    const int nB = A.nB;
+    if (unit >= (int64_t)nB * (nB + 1) / 2) return;   // the whole wave leaves
+    // unit -> (a, b), b >= a, row by row over the upper triangle of block pairs
+    int a = 0;
+    int64_t off = 0;
+    while (off + (nB - a) <= unit) {
+        off += nB - a;
+        ++a;
+    }
+    const int b = a + (int)(unit - off);
+    float3 Sh[kSymNI], Sl[kSymNI];
+    float aS[kSymNI], Su[kSymNI][KC], sacc[kSymNI][KC];
+#pragma unroll
+    for (int r = 0; r < kSymNI; ++r) {
+        const int64_t S = (int64_t)a * kSymFaces + r * 64 + lane;
+        const float4 x = A.fx[S];
+        Sh[r] = make_float3(x.x, x.y, x.z);
+        aS[r] = x.w;
+        if (HILO) {
+            const float4 l = A.fl[S];
+            Sl[r] = make_float3(l.x, l.y, l.z);
+        } else {
+            Sl[r] = make_float3(0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int c = 0; c < KC; ++c) {
+            Su[r][c] = A.ub[S * KP + c];
+            sacc[r][c] = 0.f;
+        }
+    }
+    if (a == b) {
+        sym_unit<KC, HILO, true>(A, a, b, lane, expo, Sh, Sl, aS, Su, sacc);
+    } else {
+        bool lo = HILO;
+        if (HILO) {   // blocks far apart: the high parts suffice (tile_is_far)
+            float4 ilo, ihi;
+            irange_box(A.tbox, (int64_t)a * kSymFaces, kSymFaces, ilo, ihi);
+            lo = false;
+            for (int t = 0; t < kSymFaces / kTileJ; ++t)
+                lo = lo || !tile_is_far(ilo, ihi, A.tbox, b * (kSymFaces / kTileJ) + t);
+        }
+        if (lo) sym_unit<KC, HILO, false>(A, a, b, lane, expo, Sh, Sl, aS, Su, sacc);
+        else sym_unit<KC, false, false>(A, a, b, lane, expo, Sh, Sl, aS, Su, sacc);
+    }
+#pragma unroll
+    for (int r = 0; r < kSymNI; ++r) {
+        const int64_t S = (int64_t)a * kSymFaces + r * 64 + lane;
+#pragma unroll
+        for (int c = 0; c < KC; ++c) A.part[((int64_t)b * KC + c) * A.ldp + S] = sacc[r][c];
+    }
+}
+
+// out[c][i] = sum over the nB slices, in slice order, in FP64.
+__global__ void k_reduce_sym(const float* __restrict__ part, int nB, int kc, int64_t ldp, int64_t n,
+                             double* __restrict__ out, int64_t out_stride)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * kc) return;
+    const int c = (int)(t / n);
+    const int64_t i = t - (int64_t)c * n;
+    double s = 0.0;
+    for (int sl = 0; sl < nB; ++sl) s += (double)part[((int64_t)sl * kc + c) * ldp + i];
+    out[(int64_t)c * out_stride + i] = s;
+}
+
 // ============================================================== FP64 variants
 //
 // Same structure with double pair terms and no per-tile FP32 stage.
@@ -1277,6 +1449,66 @@ static hipError_t launch_frac_k(const PairJob* jobs, int njobs, int precision, d
         else
             hipLaunchKernelGGL((k_frac32<kNiFrac32, KC, false>), grid, block, 0, s, jb, (float)expo);
     });
+}
+
+int frac_sym_block_faces() { return kSymFaces; }
+
+size_t frac_sym_part_floats(int64_t nF, int kc)
+{
+    const int64_t nB = (nF + kSymFaces - 1) / kSymFaces;
+    return (size_t)nB * (size_t)kc * (size_t)(nB * kSymFaces);
+}
+
+template <int KC>
+static void launch_frac_sym_k(const SymFracArgs& A, bool hilo, float expo, dim3 grid, hipStream_t s)
+{
+    if (hilo) hipLaunchKernelGGL((k_frac32_sym<KC, true>), grid, dim3(kBlock), 0, s, A, expo);
+    else hipLaunchKernelGGL((k_frac32_sym<KC, false>), grid, dim3(kBlock), 0, s, A, expo);
+}
+
+hipError_t launch_frac_sym(const FaceData& fd, const float* ub, float* part, int precision, double sigma, int kc,
+                           hipStream_t s)
+{
+    if (fd.nF < 1) return hipSuccess;
+    if (kc < 1 || kc > 9 || precision == TP_PREC_FP64 || !fd.tbox) return hipErrorInvalidValue;
+    SymFracArgs A;
+    A.fx = fd.fx;
+    A.fl = fd.fl;
+    A.ub = ub;
+    A.tbox = fd.tbox;
+    A.part = part;
+    A.nB = (int)((fd.nF + kSymFaces - 1) / kSymFaces);
+    A.ldp = (int64_t)A.nB * kSymFaces;
+    // the blocks read faces [0, ldp) of arrays of cap entries
+    if (A.ldp > fd.cap) return hipErrorInvalidValue;
+    const int64_t units = (int64_t)A.nB * (A.nB + 1) / 2;
+    const int64_t blocks = (units + kBlock / 64 - 1) / (kBlock / 64);
+    if (blocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks);
+    const float expo = (float)(-(2.0 * sigma + 2.0) * 0.5);   // |d|^-(2 sigma + 2) = r2^expo
+    const bool hilo = precision == TP_PREC_FP32_HILO || precision == TP_PREC_FP32_NEAR64;
+    switch (kc) {
+    case 1: launch_frac_sym_k<1>(A, hilo, expo, grid, s); break;
+    case 2: launch_frac_sym_k<2>(A, hilo, expo, grid, s); break;
+    case 3: launch_frac_sym_k<3>(A, hilo, expo, grid, s); break;
+    case 4: launch_frac_sym_k<4>(A, hilo, expo, grid, s); break;
+    case 5: launch_frac_sym_k<5>(A, hilo, expo, grid, s); break;
+    case 6: launch_frac_sym_k<6>(A, hilo, expo, grid, s); break;
+    case 7: launch_frac_sym_k<7>(A, hilo, expo, grid, s); break;
+    case 8: launch_frac_sym_k<8>(A, hilo, expo, grid, s); break;
+    default: launch_frac_sym_k<9>(A, hilo, expo, grid, s); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_sym(const float* part, int64_t nF, int kc, double* out, int64_t out_stride, hipStream_t s)
+{
+    const int64_t total = nF * kc;
+    if (total <= 0) return hipSuccess;
+    const int nB = (int)((nF + kSymFaces - 1) / kSymFaces);
+    hipLaunchKernelGGL(k_reduce_sym, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, part, nB, kc,
+                       (int64_t)nB * kSymFaces, nF, out, out_stride);
+    return hipGetLastError();
 }
 
 int near_block_faces() { return kNearFaces; }

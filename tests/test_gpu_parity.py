@@ -104,6 +104,32 @@ def test_fractional_parity(tp, meshes, k, prec):
         assert rel(L1[:, c], L0[:, c]) <= tol_for(prec), (c, rel(L1[:, c], L0[:, c]))
 
 
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("k", [1, 3, 4, 7, 9])
+@pytest.mark.parametrize("prec", [0, 1, 3])
+def test_fractional_symmetric(tp, meshes, name, k, prec):
+    """The symmetric fractional apply (each unordered pair once, for both rows) forced at
+    small sizes: against the oracle, and against the row-by-row kernel, on meshes of one
+    block (20 faces), of ragged last blocks and of two components."""
+    m = meshes[name]
+    print(f"[parity] symmetric fractional {name} k={k} precision={prec}", flush=True)
+    u = mg.random_columns(m.nV, k, 1)
+    L0 = O.fractional_apply(m.V, m.F, u, 1.0 / 3.0)
+    V, F, du = dev(m.V), dev(m.F, torch.int32), dev(u)
+    Ls = tp.tp_fractional_apply(V, F, du, tp.default_params(precision=prec, frac_sym=1)).cpu().numpy()
+    Lr = tp.tp_fractional_apply(V, F, du, tp.default_params(precision=prec, frac_sym=0)).cpu().numpy()
+    for c in range(k):
+        assert rel(Ls[:, c], L0[:, c]) <= tol_for(prec), (c, rel(Ls[:, c], L0[:, c]))
+        assert rel(Ls[:, c], Lr[:, c]) <= tol_for(prec), (c, rel(Ls[:, c], Lr[:, c]))
+
+
+def test_fractional_symmetric_errors(tp, meshes):
+    m = meshes["small_sphere"]
+    u = dev(mg.random_columns(m.nV, 1, 1))
+    with pytest.raises(tp.TpError):
+        tp.tp_fractional_apply(dev(m.V), dev(m.F, torch.int32), u, tp.default_params(frac_sym=2))
+
+
 def test_fractional_sigma_override(tp, meshes):
     m = meshes["small_sphere"]
     u = mg.random_columns(m.nV, 2, 5)
