@@ -114,7 +114,7 @@ typedef struct {
                             row), 1 symmetric at any size; symmetric means every unordered
                             pair evaluated once for both rows (the kernel's g = |d|^-(2
                             sigma + 2) is the same for both), used while its FP32 partial
-                            buffer of ceil(nF/256)^2 * 256 * k floats stays within 256 MB   */
+                            buffer of ceil(nF/256)^2 * 256 * k floats stays within 512 MB   */
 } tp_params;
 
 /* Fill *p with the defaults above. */

@@ -1350,7 +1350,7 @@ tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
 // The symmetric fractional apply (launch_frac_sym) is used for the direct FP32 sums when its
 // partial buffer stays within kSymPartBytes, and, unless forced by tp_params.frac_sym = 1,
 // from kSymMinFaces faces on, below which it has too few pairs of blocks to fill the GPU.
-constexpr double kSymPartBytes = 256.0 * 1024.0 * 1024.0;
+constexpr double kSymPartBytes = 512.0 * 1024.0 * 1024.0;
 constexpr int64_t kSymMinFaces = 16384;
 
 bool frac_sym_eligible(const tp_params& prm, int64_t nF, int kc)

@@ -594,14 +594,12 @@ __global__ __launch_bounds__(kBlock) void k_frac32(PairBatch jb, float expo)
 constexpr int kSymNI = 4;                 // faces S per lane
 constexpr int kSymFaces = 64 * kSymNI;    // faces per block: one wave's faces S
 
-// Value of the lane one below (lane 0 takes lane 63's): a rotation of the whole wave.
+// Value of the lane one below (lane 0 takes lane 63's): a rotation of the whole wave
+// (every lane has a source, so no old value is needed).
+__device__ __forceinline__ int wave_rotate(int v) { return __builtin_amdgcn_mov_dpp(v, 0x13C, 0xF, 0xF, true); }
 __device__ __forceinline__ float wave_rotate(float v)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0x13C, 0xF, 0xF, false));
-}
-__device__ __forceinline__ int wave_rotate(int v)
-{
-    return __builtin_amdgcn_update_dpp(0, v, 0x13C, 0xF, 0xF, false);
+    return __builtin_bit_cast(float, wave_rotate(__builtin_bit_cast(int, v)));
 }
 
 template <int KC, bool LO, bool DIAG>
@@ -650,7 +648,7 @@ __device__ __forceinline__ void sym_unit(const SymFracArgs& A, int a, int b, int
                 for (int c = 0; c < KC; ++c) {
                     const float diff = Su[r][c] - tu[c];
                     sacc[r][c] += gaT * diff;
-                    if (!DIAG) tacc[c] -= gaS * diff;
+                    if (!DIAG) tacc[c] += gaS * diff;   // minus row T's sum (negated on the store)
                 }
             }
             th.x = wave_rotate(th.x);
@@ -672,7 +670,7 @@ __device__ __forceinline__ void sym_unit(const SymFracArgs& A, int a, int b, int
         // 64 rotations later every face T is back in its own lane
         if (!DIAG) {
 #pragma unroll
-            for (int c = 0; c < KC; ++c) A.part[((int64_t)a * KC + c) * A.ldp + T] = tacc[c];
+            for (int c = 0; c < KC; ++c) A.part[((int64_t)a * KC + c) * A.ldp + T] = -tacc[c];
         }
     }
 }
