@@ -109,7 +109,7 @@ typedef struct {
                             that are not separated are exact (App. B: upward pass of node
                             sums, far-field products per node, downward pass to faces);
                             see tp_problem_bct_stats                                     */
-    int    frac_sym;     /* direct FP32 fractional apply: -1 (default) symmetric from 16,384
+    int    sym_pairs;     /* direct FP32 fractional apply: -1 (default) symmetric from 16,384
                             faces on, 0 row by row (every ordered pair evaluated for its
                             row), 1 symmetric at any size; symmetric means every unordered
                             pair evaluated once for both rows (the kernel's g = |d|^-(2

@@ -563,7 +563,7 @@ tp_status validate_params(const tp_params* in, tp_params& out, double& sigma)
     if (!(out.theta >= 0.0) || !std::isfinite(out.theta)) return fail(TP_E_INVALID_ARGUMENT, "theta must be finite and >= 0");
     if (out.leaf_size < 1 || out.leaf_size > 64) return fail(TP_E_INVALID_ARGUMENT, "leaf_size must lie in [1, 64]");
     if (!(out.chi >= 0.0) || !std::isfinite(out.chi)) return fail(TP_E_INVALID_ARGUMENT, "chi must be finite and >= 0");
-    if (out.frac_sym < -1 || out.frac_sym > 1) return fail(TP_E_INVALID_ARGUMENT, "frac_sym must be -1, 0 or 1");
+    if (out.sym_pairs < -1 || out.sym_pairs > 1) return fail(TP_E_INVALID_ARGUMENT, "sym_pairs must be -1, 0 or 1");
     sigma = out.sigma;
     if (sigma < 0.0) {
         const double s = (out.beta - 2.0) / out.alpha;   // s = 2 - 2/p when beta = 2 alpha
@@ -1263,6 +1263,34 @@ tp_status enqueue_near(const Batch& B, const std::vector<PairPlan>& plans, int n
     return TP_OK;
 }
 
+// The symmetric all-pairs kernels (launch_grad_sym, launch_frac_sym: each unordered pair
+// evaluated once for both rows) are used for the direct FP32 sums when their partial buffer
+// stays within kSymPartBytes, and, unless forced by tp_params.sym_pairs = 1, from
+// kSymMinFaces faces on, below which they have too few pairs of blocks to fill the GPU.
+constexpr double kSymPartBytes = 512.0 * 1024.0 * 1024.0;
+constexpr int64_t kSymMinFaces = 16384;
+constexpr int kGradOutputs = 7;   // partial sums per face of the E + dE kernels
+
+bool sym_size_ok(const tp_params& prm, int64_t nF, int nacc)
+{
+    if (prm.sym_pairs == 0 || prm.theta > 0.0 || nF < 1) return false;
+    if (4.0 * (double)frac_sym_part_floats(nF, nacc) > kSymPartBytes) return false;
+    return prm.sym_pairs == 1 || nF >= kSymMinFaces;
+}
+
+bool sym_frac_eligible(const tp_params& prm, int64_t nF, int kc)
+{
+    return prm.precision != TP_PREC_FP64 && !(prm.chi > 0.0) && kc >= 1 && kc <= kMaxGroupCols &&
+           sym_size_ok(prm, nF, kc);
+}
+
+// E + dE: the FP32 precisions with FP64 per-face sums (not the FP32-accumulator studies).
+bool sym_grad_eligible(const tp_params& prm, int64_t nF)
+{
+    const int p = prm.precision;
+    return (p == TP_PREC_FP32_HILO || p == TP_PREC_FP32 || p == TP_PREC_FP32_NEAR64) && sym_size_ok(prm, nF, kGradOutputs);
+}
+
 // E of every problem (face data must describe the point of evaluation) -> scal[slot].
 tp_status enqueue_energy(const Batch& B, int slot)
 {
@@ -1315,10 +1343,22 @@ tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
     const int prec = B[0]->prm.precision;
     std::vector<PairJob> jobs;
     std::vector<PairPlan> plans;
+    std::vector<char> sym(B.size(), 0);
     double pairs = 0;
-    for (tp_problem* P : B) {
+    for (size_t m = 0; m < B.size(); ++m) {
+        tp_problem* P = B[m];
         TP_TRY(ensure_vf(P));
-        const PairPlan pl = plan_for(kKindGrad, prec, 1, P->nF, P->cap);
+        PairPlan pl = plan_for(kKindGrad, prec, 1, P->nF, P->cap);
+        if (sym_grad_eligible(P->prm, P->nF)) {
+            // symmetric kernel; the near field (if any) goes to slice 0 of part
+            sym[m] = 1;
+            pl.n_split = 0;
+            TP_TRY(P->symp.ensure(frac_sym_part_floats(P->nF, kGradOutputs), s));
+            TP_TRY(P->part.ensure((size_t)7 * pl.irows, s));
+            TP_TRY(P->gface.ensure((size_t)7 * pl.irows, s));
+            plans.push_back(pl);
+            continue;
+        }
         const int slices = pl.n_split + (near_field(P) ? 1 : 0);
         TP_TRY(P->part.ensure((size_t)slices * 7 * pl.irows, s));
         TP_TRY(P->gface.ensure((size_t)7 * pl.irows, s));
@@ -1327,9 +1367,17 @@ tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
         plans.push_back(pl);
         pairs += (double)P->nF * (double)(P->nF - 1);
     }
-    {
+    if (!jobs.empty()) {
         PairTimer t(kKindGrad, pairs, 0.0, s);
         TP_HIP(launch_pairs_grad(jobs.data(), (int)jobs.size(), prec, B[0]->prm.alpha, B[0]->prm.beta, s));
+        t.stop();
+    }
+    for (size_t m = 0; m < B.size(); ++m) {
+        if (!sym[m]) continue;
+        tp_problem* P = B[m];
+        const double pp = (double)P->nF * (double)(P->nF - 1);
+        PairTimer t(kKindGrad, pp, 0.0, s);
+        TP_HIP(launch_grad_sym(P->fd, P->symp.p, prec, P->prm.alpha, P->prm.beta, (float)P->rho2, s));
         t.stop();
     }
     TP_TRY(enqueue_near(B, plans, 7, true));
@@ -1337,7 +1385,10 @@ tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
         tp_problem* P = B[m];
         const PairPlan& pl = plans[m];
         const int slices = pl.n_split + (near_field(P) ? 1 : 0);
-        TP_HIP(launch_reduce_splits(P->part.p, slices, 7, pl.irows, P->nF, P->gface.p, pl.irows, s));
+        if (sym[m])
+            TP_HIP(launch_reduce_sym(P->symp.p, P->nF, 7, near_field(P) ? P->part.p : nullptr, P->gface.p, pl.irows, s));
+        else
+            TP_HIP(launch_reduce_splits(P->part.p, slices, 7, pl.irows, P->nF, P->gface.p, pl.irows, s));
         TP_HIP(launch_grad_gather(P->V.p, P->F.p, P->nV, P->nF, P->vf_off.p, P->vf_idx.p, P->gface.p,
                                   pl.irows, dE[m], s));
         // 2E = sum_S a_S dE/da_S, since dE/da_S = sum_T a_T (K(S,T) + K(T,S))
@@ -1345,21 +1396,6 @@ tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
                                P->scal.p + slot, s));
     }
     return TP_OK;
-}
-
-// The symmetric fractional apply (launch_frac_sym) is used for the direct FP32 sums when its
-// partial buffer stays within kSymPartBytes, and, unless forced by tp_params.frac_sym = 1,
-// from kSymMinFaces faces on, below which it has too few pairs of blocks to fill the GPU.
-constexpr double kSymPartBytes = 512.0 * 1024.0 * 1024.0;
-constexpr int64_t kSymMinFaces = 16384;
-
-bool frac_sym_eligible(const tp_params& prm, int64_t nF, int kc)
-{
-    if (prm.frac_sym == 0 || prm.precision == TP_PREC_FP64 || prm.theta > 0.0 || prm.chi > 0.0 || kc < 1 ||
-        kc > kMaxGroupCols || nF < 1)
-        return false;
-    if (4.0 * (double)frac_sym_part_floats(nF, kc) > kSymPartBytes) return false;
-    return prm.frac_sym == 1 || nF >= kSymMinFaces;
 }
 
 // Lu[m][:, c] = (L^sigma u[m])[:, c] for k columns (row strides ldu, ldl).
@@ -1406,7 +1442,7 @@ tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, in
                                       kc, P->bh_nm.p, P->zbuf.p, pl.irows, s));
                 continue;
             }
-            if (frac_sym_eligible(P->prm, P->nF, kc)) {
+            if (sym_frac_eligible(P->prm, P->nF, kc)) {
                 TP_TRY(P->symp.ensure(frac_sym_part_floats(P->nF, kc), s));
                 sym[m] = 1;
                 continue;
@@ -1433,7 +1469,7 @@ tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, in
             tp_problem* P = B[m];
             const PairPlan& pl = plans[m];
             if (sym[m])
-                TP_HIP(launch_reduce_sym(P->symp.p, P->nF, kc, P->zbuf.p, pl.irows, s));
+                TP_HIP(launch_reduce_sym(P->symp.p, P->nF, kc, nullptr, P->zbuf.p, pl.irows, s));
             else if (!(P->prm.theta > 0.0) && !(P->prm.chi > 0.0))
                 TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, kc, pl.irows, P->nF, P->zbuf.p, pl.irows, s));
             TP_HIP(launch_ut_gather(P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->fd, P->zbuf.p, pl.irows,
@@ -2825,7 +2861,10 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
     const double gface = std::max((double)pe.irows, 7.0 * pg.irows);
     const double esz = prec == TP_PREC_FP64 ? 8 : 4;
     b += 8 * part + 8 * gface + 8.0 * kf * pf.irows + (double)cap * ((kf + 3) / 4 * 4) * esz;
-    if (frac_sym_eligible(prm, nF, kf)) b += 4.0 * (double)frac_sym_part_floats(nF, kf);
+    double symb = 0.0;
+    if (sym_frac_eligible(prm, nF, kf)) symb = 4.0 * (double)frac_sym_part_floats(nF, kf);
+    if (sym_grad_eligible(prm, nF)) symb = std::max(symb, 4.0 * (double)frac_sym_part_floats(nF, kGradOutputs));
+    b += symb;
     // step work arrays, per-face volumes and edge lengths, CG tables
     b += 8 * n * ncol * 4 + 8 * n * 3 * 3 + 16 * f + 4096;
     // Barnes-Hut tree, keys, sort scratch and per-face sums (allocated at creation, where
@@ -2925,7 +2964,7 @@ tp_status tp_params_default(tp_params* p)
     p->theta = 0.0;
     p->leaf_size = 8;
     p->chi = 0.0;
-    p->frac_sym = -1;
+    p->sym_pairs = -1;
     return TP_OK;
 }
 

@@ -159,7 +159,13 @@ size_t frac_sym_part_floats(int64_t nF, int kc);
 // TP_PREC_FP64), then the sums over the slices: out[c * out_stride + i] for i < nF.
 hipError_t launch_frac_sym(const FaceData& fd, const float* ub, float* part, int precision, double sigma, int kc,
                            hipStream_t s);
-hipError_t launch_reduce_sym(const float* part, int64_t nF, int kc, double* out, int64_t out_stride, hipStream_t s);
+hipError_t launch_reduce_sym(const float* part, int64_t nF, int kc, const double* extra, double* out,
+                             int64_t out_stride, hipStream_t s);
+// Symmetric E + dE (each unordered pair once, both rows; FP32 pair terms): the seven outputs
+// per face and slice into part ([nB][7][ldp] FP32, frac_sym_part_floats(nF, 7) entries);
+// with TP_PREC_FP32_NEAR64 pairs closer than sqrt(rho2) are left to the near field.
+hipError_t launch_grad_sym(const FaceData& fd, float* part, int precision, double alpha, double beta, float rho2,
+                           hipStream_t s);
 
 hipError_t launch_reduce_splits(const double* part, int n_split, int nacc, int64_t irows,
                                 int64_t n, double* out, int64_t out_stride, hipStream_t s);

@@ -733,9 +733,207 @@ __global__ __launch_bounds__(kBlock) void k_frac32_sym(SymFracArgs A, float expo
     }
 }
 
-// out[c][i] = sum over the nB slices, in slice order, in FP64.
+// ============================================================== symmetric E + dE (FP32)
+//
+// The same scheme for the energy's differential: an unordered pair (S, T) gives row S's
+// eleven sums and row T's.  Seen from T, d, N_T.d and N_S.d change sign exactly, so K and
+// K' are shared and the q-derivatives change sign; row T's terms are row S's formulas with
+// a_S, N_S in place of a_T, N_T and those signs, bit for bit the terms its own evaluation
+// would give.  Row T's first seven sums are kept negated so that every update is a plain
+// multiply-add, and put right in the epilogue.
+
+struct GSymArgs {
+    const float4* fx = nullptr;
+    const float4* fl = nullptr;
+    const float4* fn = nullptr;
+    const double4* dx = nullptr;
+    const double4* dn = nullptr;
+    const float4* tbox = nullptr;
+    float* part = nullptr;    // [nB][kGradOut][ldp]
+    int64_t ldp = 0;
+    int nB = 0;
+    float rho2 = 0.f;
+};
+
+// The seven outputs of a face from its eleven sums (FP64, as in k_grad32), into slice sl.
+__device__ __forceinline__ void gsym_store(const GSymArgs& A, int sl, int64_t f, const float (&c)[kGradAcc],
+                                           double alpha, double beta)
+{
+    const double aF = A.dx[f].w;
+    const double4 N = A.dn[f];
+    double a[kGradAcc];
+#pragma unroll
+    for (int m = 0; m < kGradAcc; ++m) a[m] = (double)c[m];
+    float* dst = A.part + (int64_t)sl * kGradOut * A.ldp + f;
+    dst[0 * A.ldp] = (float)(aF * (alpha * (N.x * a[0] + a[1]) - beta * a[4]));
+    dst[1 * A.ldp] = (float)(aF * (alpha * (N.y * a[0] + a[2]) - beta * a[5]));
+    dst[2 * A.ldp] = (float)(aF * (alpha * (N.z * a[0] + a[3]) - beta * a[6]));
+    dst[3 * A.ldp] = (float)(aF * alpha * a[7]);
+    dst[4 * A.ldp] = (float)(aF * alpha * a[8]);
+    dst[5 * A.ldp] = (float)(aF * alpha * a[9]);
+    dst[6 * A.ldp] = (float)a[10];
+}
+
+template <bool LO, bool NEAR, bool DIAG, class Pow>
+__device__ __forceinline__ void gsym_unit(const GSymArgs& A, int a, int b, int lane, const Pow& pw, double alpha,
+                                          double beta, const float3 (&Sh)[kSymNI], const float3 (&Sl)[kSymNI],
+                                          const float3 (&Sn)[kSymNI], const float (&aS)[kSymNI],
+                                          float (&c)[kSymNI][kGradAcc])
+{
+    for (int q = 0; q < kSymFaces / 64; ++q) {
+        const int64_t T = (int64_t)b * kSymFaces + q * 64 + lane;
+        float4 th = A.fx[T];
+        float3 tl = make_float3(0.f, 0.f, 0.f);
+        if (LO) {
+            const float4 l = A.fl[T];
+            tl = make_float3(l.x, l.y, l.z);
+        }
+        const float4 n4 = A.fn[T];
+        float3 tn = make_float3(n4.x, n4.y, n4.z);
+        float ct[kGradAcc];
+#pragma unroll
+        for (int m = 0; m < kGradAcc; ++m) ct[m] = 0.f;
+        int ti = (int)T;
+#pragma unroll 1
+        for (int step = 0; step < 64; ++step) {
+#pragma unroll
+            for (int r = 0; r < kSymNI; ++r) {
+                float dx, dy, dz;
+                if (LO) {
+                    dx = (Sh[r].x - th.x) + (Sl[r].x - tl.x);
+                    dy = (Sh[r].y - th.y) + (Sl[r].y - tl.y);
+                    dz = (Sh[r].z - th.z) + (Sl[r].z - tl.z);
+                } else {
+                    dx = Sh[r].x - th.x;
+                    dy = Sh[r].y - th.y;
+                    dz = Sh[r].z - th.z;
+                }
+                float r2 = dist2_32(dx, dy, dz);
+                if (DIAG) r2 = ((int)((int64_t)a * kSymFaces + r * 64 + lane) == ti) ? 1.0f : r2;
+                if (NEAR) r2 = r2 < A.rho2 ? INFINITY : r2;   // summed by the FP64 near field
+                const float inv = rcp_fast(r2);
+                const float qs = Sn[r].x * dx + Sn[r].y * dy + Sn[r].z * dz;
+                const float qt = tn.x * dx + tn.y * dy + tn.z * dz;
+                float K, Kqr, Kp, Kpqr;
+                pw.KG(qs, r2, inv, K, Kqr);
+                pw.KG(qt, r2, inv, Kp, Kpqr);
+                const float KK = K + Kp;
+                // row S, as k_grad32 forms it
+                const float t = th.w * inv;
+                const float aq = Kqr * t, ap = Kpqr * t, cc = KK * t;
+                c[r][0] += aq;
+                c[r][1] += ap * tn.x;
+                c[r][2] += ap * tn.y;
+                c[r][3] += ap * tn.z;
+                c[r][4] += cc * dx;
+                c[r][5] += cc * dy;
+                c[r][6] += cc * dz;
+                c[r][7] += aq * dx;
+                c[r][8] += aq * dy;
+                c[r][9] += aq * dz;
+                c[r][10] += KK * th.w;
+                if (!DIAG) {
+                    // row T: sums 0..6 negated
+                    const float ts = aS[r] * inv;
+                    const float bq = Kpqr * ts, bp = Kqr * ts, cs = KK * ts;
+                    ct[0] += bq;
+                    ct[1] += bp * Sn[r].x;
+                    ct[2] += bp * Sn[r].y;
+                    ct[3] += bp * Sn[r].z;
+                    ct[4] += cs * dx;
+                    ct[5] += cs * dy;
+                    ct[6] += cs * dz;
+                    ct[7] += bq * dx;
+                    ct[8] += bq * dy;
+                    ct[9] += bq * dz;
+                    ct[10] += KK * aS[r];
+                }
+            }
+            th.x = wave_rotate(th.x);
+            th.y = wave_rotate(th.y);
+            th.z = wave_rotate(th.z);
+            th.w = wave_rotate(th.w);
+            if (LO) {
+                tl.x = wave_rotate(tl.x);
+                tl.y = wave_rotate(tl.y);
+                tl.z = wave_rotate(tl.z);
+            }
+            tn.x = wave_rotate(tn.x);
+            tn.y = wave_rotate(tn.y);
+            tn.z = wave_rotate(tn.z);
+            if (!DIAG) {
+#pragma unroll
+                for (int m = 0; m < kGradAcc; ++m) ct[m] = wave_rotate(ct[m]);
+            }
+            if (DIAG || NEAR) ti = wave_rotate(ti);
+        }
+        if (!DIAG) {
+#pragma unroll
+            for (int m = 0; m < 7; ++m) ct[m] = -ct[m];
+            gsym_store(A, a, T, ct, alpha, beta);
+        }
+    }
+}
+
+template <bool HILO, bool NEAR, class Pow>
+__global__ __launch_bounds__(kBlock) void k_grad32_sym(GSymArgs A, double alpha, double beta, Pow pw)
+{
+    const int lane = (int)threadIdx.x & 63;
+    const int64_t unit = (int64_t)blockIdx.x * (kBlock / 64) + ((int)threadIdx.x >> 6);
+    const int nB = A.nB;
+    if (unit >= (int64_t)nB * (nB + 1) / 2) return;   // the whole wave leaves
+    int a = 0;
+    int64_t off = 0;
+    while (off + (nB - a) <= unit) {
+        off += nB - a;
+        ++a;
+    }
+    const int b = a + (int)(unit - off);
+    float3 Sh[kSymNI], Sl[kSymNI], Sn[kSymNI];
+    float aS[kSymNI], c[kSymNI][kGradAcc];
+#pragma unroll
+    for (int r = 0; r < kSymNI; ++r) {
+        const int64_t S = (int64_t)a * kSymFaces + r * 64 + lane;
+        const float4 x = A.fx[S], n = A.fn[S];
+        Sh[r] = make_float3(x.x, x.y, x.z);
+        Sn[r] = make_float3(n.x, n.y, n.z);
+        aS[r] = x.w;
+        if (HILO) {
+            const float4 l = A.fl[S];
+            Sl[r] = make_float3(l.x, l.y, l.z);
+        } else {
+            Sl[r] = make_float3(0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int m = 0; m < kGradAcc; ++m) c[r][m] = 0.f;
+    }
+    // the block pair's tile tests, as k_grad32 makes them for a tile
+    bool near = false, far = HILO;
+    if (NEAR || HILO) {
+        float4 ilo, ihi;
+        irange_box(A.tbox, (int64_t)a * kSymFaces, kSymFaces, ilo, ihi);
+        for (int t = 0; t < kSymFaces / kTileJ; ++t) {
+            const int jt = b * (kSymFaces / kTileJ) + t;
+            if (NEAR) near = near || tile_may_be_near(ilo, ihi, A.tbox, jt, A.rho2);
+            if (HILO) far = far && tile_is_far(ilo, ihi, A.tbox, jt);
+        }
+    }
+    if (a == b)
+        gsym_unit<HILO, NEAR, true>(A, a, b, lane, pw, alpha, beta, Sh, Sl, Sn, aS, c);
+    else if (NEAR && near)
+        gsym_unit<HILO, NEAR, false>(A, a, b, lane, pw, alpha, beta, Sh, Sl, Sn, aS, c);
+    else if (HILO && far)
+        gsym_unit<false, false, false>(A, a, b, lane, pw, alpha, beta, Sh, Sl, Sn, aS, c);
+    else
+        gsym_unit<HILO, false, false>(A, a, b, lane, pw, alpha, beta, Sh, Sl, Sn, aS, c);
+#pragma unroll
+    for (int r = 0; r < kSymNI; ++r) gsym_store(A, b, (int64_t)a * kSymFaces + r * 64 + lane, c[r], alpha, beta);
+}
+
+// out[c][i] = sum over the nB slices, in slice order, in FP64 (then extra[c][i], the FP64
+// near field, when given).
 __global__ void k_reduce_sym(const float* __restrict__ part, int nB, int kc, int64_t ldp, int64_t n,
-                             double* __restrict__ out, int64_t out_stride)
+                             const double* __restrict__ extra, double* __restrict__ out, int64_t out_stride)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n * kc) return;
@@ -743,6 +941,7 @@ __global__ void k_reduce_sym(const float* __restrict__ part, int nB, int kc, int
     const int64_t i = t - (int64_t)c * n;
     double s = 0.0;
     for (int sl = 0; sl < nB; ++sl) s += (double)part[((int64_t)sl * kc + c) * ldp + i];
+    if (extra) s += extra[(int64_t)c * out_stride + i];
     out[(int64_t)c * out_stride + i] = s;
 }
 
@@ -1499,13 +1698,51 @@ hipError_t launch_frac_sym(const FaceData& fd, const float* ub, float* part, int
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_sym(const float* part, int64_t nF, int kc, double* out, int64_t out_stride, hipStream_t s)
+hipError_t launch_reduce_sym(const float* part, int64_t nF, int kc, const double* extra, double* out,
+                             int64_t out_stride, hipStream_t s)
 {
     const int64_t total = nF * kc;
     if (total <= 0) return hipSuccess;
     const int nB = (int)((nF + kSymFaces - 1) / kSymFaces);
     hipLaunchKernelGGL(k_reduce_sym, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, part, nB, kc,
-                       (int64_t)nB * kSymFaces, nF, out, out_stride);
+                       (int64_t)nB * kSymFaces, nF, extra, out, out_stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_sym(const FaceData& fd, float* part, int precision, double alpha, double beta, float rho2,
+                           hipStream_t s)
+{
+    if (fd.nF < 1) return hipSuccess;
+    if (precision == TP_PREC_FP64 || !fd.tbox) return hipErrorInvalidValue;
+    GSymArgs A;
+    A.fx = fd.fx;
+    A.fl = fd.fl;
+    A.fn = fd.fn;
+    A.dx = fd.dx;
+    A.dn = fd.dn;
+    A.tbox = fd.tbox;
+    A.part = part;
+    A.nB = (int)((fd.nF + kSymFaces - 1) / kSymFaces);
+    A.ldp = (int64_t)A.nB * kSymFaces;
+    A.rho2 = rho2;
+    if (A.ldp > fd.cap) return hipErrorInvalidValue;
+    const int64_t units = (int64_t)A.nB * (A.nB + 1) / 2;
+    const int64_t blocks = (units + kBlock / 64 - 1) / (kBlock / 64);
+    if (blocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks), block(kBlock);
+    const bool hilo = precision == TP_PREC_FP32_HILO || precision == TP_PREC_FP32_NEAR64;
+    const bool near = precision == TP_PREC_FP32_NEAR64;
+    if (is_p6(alpha, beta)) {
+        const PowP6 pw;
+        if (near) hipLaunchKernelGGL((k_grad32_sym<true, true, PowP6>), grid, block, 0, s, A, alpha, beta, pw);
+        else if (hilo) hipLaunchKernelGGL((k_grad32_sym<true, false, PowP6>), grid, block, 0, s, A, alpha, beta, pw);
+        else hipLaunchKernelGGL((k_grad32_sym<false, false, PowP6>), grid, block, 0, s, A, alpha, beta, pw);
+    } else {
+        const PowGen pw = make_gen(alpha, beta);
+        if (near) hipLaunchKernelGGL((k_grad32_sym<true, true, PowGen>), grid, block, 0, s, A, alpha, beta, pw);
+        else if (hilo) hipLaunchKernelGGL((k_grad32_sym<true, false, PowGen>), grid, block, 0, s, A, alpha, beta, pw);
+        else hipLaunchKernelGGL((k_grad32_sym<false, false, PowGen>), grid, block, 0, s, A, alpha, beta, pw);
+    }
     return hipGetLastError();
 }
 

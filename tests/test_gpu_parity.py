@@ -91,6 +91,39 @@ def test_general_exponents(tp, meshes, alpha, beta, prec):
         assert abs(E2 - E0) <= t * E0
 
 
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("prec", [0, 1, 3])
+def test_gradient_symmetric(tp, meshes, name, prec):
+    """The symmetric E + dE kernel (each unordered pair once, for both rows) forced at small
+    sizes: E and dE against the oracle and against the row-by-row kernel, on meshes of one
+    block, of ragged last blocks and of two components, with and without the FP64 near
+    field."""
+    m = meshes[name]
+    print(f"[parity] symmetric gradient {name} precision={prec}", flush=True)
+    E0, g0 = O.gradient(m.V, m.F)
+    V, F = dev(m.V), dev(m.F, torch.int32)
+    Es, gs = tp.tp_gradient(V, F, tp.default_params(precision=prec, sym_pairs=1))
+    Er, gr = tp.tp_gradient(V, F, tp.default_params(precision=prec, sym_pairs=0))
+    gs, gr = gs.cpu().numpy(), gr.cpu().numpy()
+    t = tol_for(prec)
+    assert abs(Es - E0) <= t * E0, (Es, E0)
+    assert rel(gs, g0) <= t, rel(gs, g0)
+    assert abs(Es - Er) <= t * E0, (Es, Er)
+    assert rel(gs, gr) <= t, rel(gs, gr)
+
+
+@pytest.mark.parametrize("alpha,beta", [(4.0, 9.0), (8.0, 16.0)])
+def test_gradient_symmetric_general_exponents(tp, meshes, alpha, beta):
+    m = meshes["geodesic9"]
+    print(f"[parity] symmetric gradient alpha={alpha} beta={beta}", flush=True)
+    E0, g0 = O.gradient(m.V, m.F, alpha, beta)
+    p = tp.default_params(alpha=alpha, beta=beta, precision=0, sym_pairs=1)
+    E1, g1 = tp.tp_gradient(dev(m.V), dev(m.F, torch.int32), p)
+    t = tol_for(0)
+    assert abs(E1 - E0) <= t * E0
+    assert rel(g1.cpu().numpy(), g0) <= t
+
+
 @pytest.mark.parametrize("k", [1, 3, 9, 11])
 @pytest.mark.parametrize("prec", [0, 1, 2])
 def test_fractional_parity(tp, meshes, k, prec):
@@ -116,8 +149,8 @@ def test_fractional_symmetric(tp, meshes, name, k, prec):
     u = mg.random_columns(m.nV, k, 1)
     L0 = O.fractional_apply(m.V, m.F, u, 1.0 / 3.0)
     V, F, du = dev(m.V), dev(m.F, torch.int32), dev(u)
-    Ls = tp.tp_fractional_apply(V, F, du, tp.default_params(precision=prec, frac_sym=1)).cpu().numpy()
-    Lr = tp.tp_fractional_apply(V, F, du, tp.default_params(precision=prec, frac_sym=0)).cpu().numpy()
+    Ls = tp.tp_fractional_apply(V, F, du, tp.default_params(precision=prec, sym_pairs=1)).cpu().numpy()
+    Lr = tp.tp_fractional_apply(V, F, du, tp.default_params(precision=prec, sym_pairs=0)).cpu().numpy()
     for c in range(k):
         assert rel(Ls[:, c], L0[:, c]) <= tol_for(prec), (c, rel(Ls[:, c], L0[:, c]))
         assert rel(Ls[:, c], Lr[:, c]) <= tol_for(prec), (c, rel(Ls[:, c], Lr[:, c]))
@@ -127,7 +160,7 @@ def test_fractional_symmetric_errors(tp, meshes):
     m = meshes["small_sphere"]
     u = dev(mg.random_columns(m.nV, 1, 1))
     with pytest.raises(tp.TpError):
-        tp.tp_fractional_apply(dev(m.V), dev(m.F, torch.int32), u, tp.default_params(frac_sym=2))
+        tp.tp_fractional_apply(dev(m.V), dev(m.F, torch.int32), u, tp.default_params(sym_pairs=2))
 
 
 def test_fractional_sigma_override(tp, meshes):
