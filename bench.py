@@ -42,9 +42,9 @@ PEAK_HBM_GBS = 8000.0
 GRAD_TRAFFIC = {
     "sources": ["paper_2107_01664_amd/csrc/tp_pairs.hip", "paper_2107_01664_amd/csrc/tp_tiles.h",
                 "paper_2107_01664_amd/csrc/tp_internal.h"],
-    "sha256": "5bd7a8862143e8ee7c5789495fd4e7e1c91c7340e3f8af50ad4e9328b11fe77e",
-    "fetch_bytes": int(55042.640625 * 1024) * 2,
-    "write_bytes": 64148 * 1024,
+    "sha256": "04efc31c0d3a2371e0e326757441889dc59c6d8b5a70930dbbc5177fe8dd6825",
+    "fetch_bytes": int(61912.0625 * 1024) * 2,
+    "write_bytes": 172543 * 1024,
 }
 
 
@@ -645,7 +645,7 @@ def main():
         },
         "roofline": {
             "bound": "alu",
-            "kernel": "all-pairs energy + differential",
+            "kernel": "all-pairs energy + differential (k_grad32_sym: each unordered pair once, for both rows)",
             "achieved": grad_tflops,
             "peak": PEAK_FP32_VALU_TFLOPS,
             "unit": "TFLOP/s",
