@@ -602,6 +602,25 @@ __device__ __forceinline__ float wave_rotate(float v)
     return __builtin_bit_cast(float, wave_rotate(__builtin_bit_cast(int, v)));
 }
 
+// The pair of blocks (a, b), b >= a, of a wave's unit: the nB (nB - 1) / 2 pairs a < b
+// first, row by row, then the nB diagonal ones, which do one side only and so make a
+// lighter last round.
+__device__ __forceinline__ void sym_unit_blocks(int64_t unit, int nB, int& a, int& b)
+{
+    const int64_t noff = (int64_t)nB * (nB - 1) / 2;
+    if (unit >= noff) {
+        a = b = (int)(unit - noff);
+        return;
+    }
+    a = 0;
+    int64_t off = 0;
+    while (off + (nB - 1 - a) <= unit) {
+        off += nB - 1 - a;
+        ++a;
+    }
+    b = a + 1 + (int)(unit - off);
+}
+
 template <int KC, bool LO, bool DIAG>
 __device__ __forceinline__ void sym_unit(const SymFracArgs& A, int a, int b, int lane, float expo,
                                          const float3 (&Sh)[kSymNI], const float3 (&Sl)[kSymNI],
@@ -683,14 +702,8 @@ __global__ __launch_bounds__(kBlock) void k_frac32_sym(SymFracArgs A, float expo
     const int64_t unit = (int64_t)blockIdx.x * (kBlock / 64) + ((int)threadIdx.x >> 6);
     const int nB = A.nB;
     if (unit >= (int64_t)nB * (nB + 1) / 2) return;   // the whole wave leaves
-    // unit -> (a, b), b >= a, row by row over the upper triangle of block pairs
-    int a = 0;
-    int64_t off = 0;
-    while (off + (nB - a) <= unit) {
-        off += nB - a;
-        ++a;
-    }
-    const int b = a + (int)(unit - off);
+    int a, b;
+    sym_unit_blocks(unit, nB, a, b);
     float3 Sh[kSymNI], Sl[kSymNI];
     float aS[kSymNI], Su[kSymNI][KC], sacc[kSymNI][KC];
 #pragma unroll
@@ -865,7 +878,7 @@ __device__ __forceinline__ void gsym_unit(const GSymArgs& A, int a, int b, int l
 #pragma unroll
                 for (int m = 0; m < kGradAcc; ++m) ct[m] = wave_rotate(ct[m]);
             }
-            if (DIAG || NEAR) ti = wave_rotate(ti);
+            if (DIAG) ti = wave_rotate(ti);
         }
         if (!DIAG) {
 #pragma unroll
@@ -882,13 +895,8 @@ __global__ __launch_bounds__(kBlock) void k_grad32_sym(GSymArgs A, double alpha,
     const int64_t unit = (int64_t)blockIdx.x * (kBlock / 64) + ((int)threadIdx.x >> 6);
     const int nB = A.nB;
     if (unit >= (int64_t)nB * (nB + 1) / 2) return;   // the whole wave leaves
-    int a = 0;
-    int64_t off = 0;
-    while (off + (nB - a) <= unit) {
-        off += nB - a;
-        ++a;
-    }
-    const int b = a + (int)(unit - off);
+    int a, b;
+    sym_unit_blocks(unit, nB, a, b);
     float3 Sh[kSymNI], Sl[kSymNI], Sn[kSymNI];
     float aS[kSymNI], c[kSymNI][kGradAcc];
 #pragma unroll
