@@ -42,8 +42,8 @@ PEAK_HBM_GBS = 8000.0
 GRAD_TRAFFIC = {
     "sources": ["paper_2107_01664_amd/csrc/tp_pairs.hip", "paper_2107_01664_amd/csrc/tp_tiles.h",
                 "paper_2107_01664_amd/csrc/tp_internal.h"],
-    "sha256": "04efc31c0d3a2371e0e326757441889dc59c6d8b5a70930dbbc5177fe8dd6825",
-    "fetch_bytes": int(61912.0625 * 1024) * 2,
+    "sha256": "3cf8fc144c7318a12dbec2071674a66e90d99bebe49d86435a4cf5cd3fa5cd56",
+    "fetch_bytes": int(59240.0 * 1024) * 2,
     "write_bytes": 172543 * 1024,
 }
 

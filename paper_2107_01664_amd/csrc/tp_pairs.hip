@@ -584,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_frac32(PairBatch jb, float expo)
 // bits).  Here every unordered pair is evaluated once and adds to both rows.  Faces are
 // cut into blocks of kSymFaces; a wave takes one pair of blocks (a, b), b >= a: its 64
 // lanes hold the kSymNI faces S of block a each, and the faces T of block b pass along the
-// wave 64 at a time, one lane a step (a full-wave DPP rotation), carrying their own column
+// wave 64 at a time, one lane a step (a rotation of the whole wave), carrying their own column
 // sums.  For b > a both rows collect; the diagonal blocks (b = a) are summed row by row
 // (S-side only, S = T left out), as in k_frac32.  A wave writes its S-side sums to slice b
 // and its T-side sums to slice a of an FP32 partial buffer [nB][kc][ldp]: every face gets
@@ -594,13 +594,19 @@ __global__ __launch_bounds__(kBlock) void k_frac32(PairBatch jb, float expo)
 constexpr int kSymNI = 4;                 // faces S per lane
 constexpr int kSymFaces = 64 * kSymNI;    // faces per block: one wave's faces S
 
-// Value of the lane one below (lane 0 takes lane 63's): a rotation of the whole wave
-// (every lane has a source, so no old value is needed).
-__device__ __forceinline__ int wave_rotate(int v) { return __builtin_amdgcn_mov_dpp(v, 0x13C, 0xF, 0xF, true); }
-__device__ __forceinline__ float wave_rotate(float v)
-{
-    return __builtin_bit_cast(float, wave_rotate(__builtin_bit_cast(int, v)));
-}
+// Value of the lane one below (lane 0 takes lane 63's): a rotation of the whole wave through
+// the LDS crossbar (ds_bpermute).  The pair loops are bound by vector-ALU issue (about one
+// wave-instruction per CU and clock, measured), and a DPP move would take one of those
+// slots per value; ds_bpermute takes none, only LDS bandwidth, which these loops leave idle.
+struct WaveRot {
+    int addr;   // byte address of the source lane
+    __device__ __forceinline__ explicit WaveRot(int lane) : addr(((lane + 63) & 63) << 2) {}
+    __device__ __forceinline__ int operator()(int v) const { return __builtin_amdgcn_ds_bpermute(addr, v); }
+    __device__ __forceinline__ float operator()(float v) const
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
+    }
+};
 
 // The pair of blocks (a, b), b >= a, of a wave's unit: the nB (nB - 1) / 2 pairs a < b
 // first, row by row, then the nB diagonal ones, which do one side only and so make a
@@ -629,6 +635,7 @@ __device__ __forceinline__ void sym_unit(const SymFracArgs& A, int a, int b, int
 {
     constexpr int KP = KPad<KC>::value;
     const float* __restrict__ ub = A.ub;
+    const WaveRot rot(lane);
     for (int q = 0; q < kSymFaces / 64; ++q) {
         const int64_t T = (int64_t)b * kSymFaces + q * 64 + lane;
         float4 th = A.fx[T];
@@ -670,21 +677,21 @@ __device__ __forceinline__ void sym_unit(const SymFracArgs& A, int a, int b, int
                     if (!DIAG) tacc[c] += gaS * diff;   // minus row T's sum (negated on the store)
                 }
             }
-            th.x = wave_rotate(th.x);
-            th.y = wave_rotate(th.y);
-            th.z = wave_rotate(th.z);
-            th.w = wave_rotate(th.w);
+            th.x = rot(th.x);
+            th.y = rot(th.y);
+            th.z = rot(th.z);
+            th.w = rot(th.w);
             if (LO) {
-                tl.x = wave_rotate(tl.x);
-                tl.y = wave_rotate(tl.y);
-                tl.z = wave_rotate(tl.z);
+                tl.x = rot(tl.x);
+                tl.y = rot(tl.y);
+                tl.z = rot(tl.z);
             }
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
-                tu[c] = wave_rotate(tu[c]);
-                if (!DIAG) tacc[c] = wave_rotate(tacc[c]);
+                tu[c] = rot(tu[c]);
+                if (!DIAG) tacc[c] = rot(tacc[c]);
             }
-            if (DIAG) ti = wave_rotate(ti);
+            if (DIAG) ti = rot(ti);
         }
         // 64 rotations later every face T is back in its own lane
         if (!DIAG) {
@@ -793,6 +800,7 @@ __device__ __forceinline__ void gsym_unit(const GSymArgs& A, int a, int b, int l
                                           const float3 (&Sn)[kSymNI], const float (&aS)[kSymNI],
                                           float (&c)[kSymNI][kGradAcc])
 {
+    const WaveRot rot(lane);
     for (int q = 0; q < kSymFaces / 64; ++q) {
         const int64_t T = (int64_t)b * kSymFaces + q * 64 + lane;
         float4 th = A.fx[T];
@@ -862,23 +870,23 @@ __device__ __forceinline__ void gsym_unit(const GSymArgs& A, int a, int b, int l
                     ct[10] += KK * aS[r];
                 }
             }
-            th.x = wave_rotate(th.x);
-            th.y = wave_rotate(th.y);
-            th.z = wave_rotate(th.z);
-            th.w = wave_rotate(th.w);
+            th.x = rot(th.x);
+            th.y = rot(th.y);
+            th.z = rot(th.z);
+            th.w = rot(th.w);
             if (LO) {
-                tl.x = wave_rotate(tl.x);
-                tl.y = wave_rotate(tl.y);
-                tl.z = wave_rotate(tl.z);
+                tl.x = rot(tl.x);
+                tl.y = rot(tl.y);
+                tl.z = rot(tl.z);
             }
-            tn.x = wave_rotate(tn.x);
-            tn.y = wave_rotate(tn.y);
-            tn.z = wave_rotate(tn.z);
+            tn.x = rot(tn.x);
+            tn.y = rot(tn.y);
+            tn.z = rot(tn.z);
             if (!DIAG) {
 #pragma unroll
-                for (int m = 0; m < kGradAcc; ++m) ct[m] = wave_rotate(ct[m]);
+                for (int m = 0; m < kGradAcc; ++m) ct[m] = rot(ct[m]);
             }
-            if (DIAG) ti = wave_rotate(ti);
+            if (DIAG) ti = rot(ti);
         }
         if (!DIAG) {
 #pragma unroll
