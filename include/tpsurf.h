@@ -113,8 +113,14 @@ typedef struct {
                             faces on, 0 row by row (every ordered pair evaluated for its
                             row), 1 symmetric at any size; symmetric means every unordered
                             pair evaluated once for both rows (the kernel's g = |d|^-(2
-                            sigma + 2) is the same for both), used while its FP32 partial
-                            buffer of ceil(nF/256)^2 * 256 * k floats stays within 512 MB   */
+                            sigma + 2) is the same for both); the same choice for E + dE    */
+    int    sym_band;      /* the symmetric kernels take the rows of 256-face blocks in bands,
+                            one launch and one FP64 reduction per band, so that their FP32
+                            partial buffer (2 * band * k * nF floats, or ceil(nF/256) * k *
+                            nF with one band) stays within 512 MB; 0 (default): the tallest
+                            such band; > 0: at most that many blocks per band.  The sums
+                            are added in the same order for every band height, so results
+                            do not depend on it                                            */
 } tp_params;
 
 /* Fill *p with the defaults above. */

@@ -564,6 +564,7 @@ tp_status validate_params(const tp_params* in, tp_params& out, double& sigma)
     if (out.leaf_size < 1 || out.leaf_size > 64) return fail(TP_E_INVALID_ARGUMENT, "leaf_size must lie in [1, 64]");
     if (!(out.chi >= 0.0) || !std::isfinite(out.chi)) return fail(TP_E_INVALID_ARGUMENT, "chi must be finite and >= 0");
     if (out.sym_pairs < -1 || out.sym_pairs > 1) return fail(TP_E_INVALID_ARGUMENT, "sym_pairs must be -1, 0 or 1");
+    if (out.sym_band < 0) return fail(TP_E_INVALID_ARGUMENT, "sym_band must be >= 0");
     sigma = out.sigma;
     if (sigma < 0.0) {
         const double s = (out.beta - 2.0) / out.alpha;   // s = 2 - 2/p when beta = 2 alpha
@@ -1264,18 +1265,46 @@ tp_status enqueue_near(const Batch& B, const std::vector<PairPlan>& plans, int n
 }
 
 // The symmetric all-pairs kernels (launch_grad_sym, launch_frac_sym: each unordered pair
-// evaluated once for both rows) are used for the direct FP32 sums when their partial buffer
-// stays within kSymPartBytes, and, unless forced by tp_params.sym_pairs = 1, from
-// kSymMinFaces faces on, below which they have too few pairs of blocks to fill the GPU.
+// evaluated once for both rows) are used for the direct FP32 sums, unless forced by
+// tp_params.sym_pairs = 1, from kSymMinFaces faces on, below which they have too few pairs
+// of blocks to fill the GPU.  Their partial buffer is kept within kSymPartBytes by running
+// the rows in bands (one launch and one reduction per band; a single band up to about
+// 68,000 faces for E + dE).
 constexpr double kSymPartBytes = 512.0 * 1024.0 * 1024.0;
 constexpr int64_t kSymMinFaces = 16384;
 constexpr int kGradOutputs = 7;   // partial sums per face of the E + dE kernels
 
 bool sym_size_ok(const tp_params& prm, int64_t nF, int nacc)
 {
+    (void)nacc;
     if (prm.sym_pairs == 0 || prm.theta > 0.0 || nF < 1) return false;
-    if (4.0 * (double)frac_sym_part_floats(nF, nacc) > kSymPartBytes) return false;
     return prm.sym_pairs == 1 || nF >= kSymMinFaces;
+}
+
+int sym_band_height(const tp_params& prm, int64_t nF, int kc)
+{
+    const int K = sym_band_blocks(nF, kc, kSymPartBytes);
+    return prm.sym_band > 0 ? std::min(K, prm.sym_band) : K;
+}
+
+size_t sym_buffer_floats(const tp_params& prm, int64_t nF, int kc)
+{
+    return sym_part_floats(nF, kc, sym_band_height(prm, nF, kc));
+}
+
+// The bands of rows of a symmetric launch over nF faces with kc sums per face: fn(K, a0, a1,
+// share of the unordered pairs) for each band in order.
+template <class Fn>
+tp_status for_each_sym_band(const tp_params& prm, int64_t nF, int kc, Fn&& fn)
+{
+    const int nB = (int)((nF + frac_sym_block_faces() - 1) / frac_sym_block_faces());
+    const int K = sym_band_height(prm, nF, kc);
+    const double total = (double)sym_band_units(nF, 0, nB);
+    for (int a0 = 0; a0 < nB; a0 += K) {
+        const int a1 = std::min(nB, a0 + K);
+        TP_TRY(fn(K, a0, a1, (double)sym_band_units(nF, a0, a1) / total));
+    }
+    return TP_OK;
 }
 
 bool sym_frac_eligible(const tp_params& prm, int64_t nF, int kc)
@@ -1353,7 +1382,7 @@ tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
             // symmetric kernel; the near field (if any) goes to slice 0 of part
             sym[m] = 1;
             pl.n_split = 0;
-            TP_TRY(P->symp.ensure(frac_sym_part_floats(P->nF, kGradOutputs), s));
+            TP_TRY(P->symp.ensure(sym_buffer_floats(P->prm, P->nF, kGradOutputs), s));
             TP_TRY(P->part.ensure((size_t)7 * pl.irows, s));
             TP_TRY(P->gface.ensure((size_t)7 * pl.irows, s));
             plans.push_back(pl);
@@ -1372,22 +1401,27 @@ tp_status enqueue_gradient(const Batch& B, double* const* dE, int slot)
         TP_HIP(launch_pairs_grad(jobs.data(), (int)jobs.size(), prec, B[0]->prm.alpha, B[0]->prm.beta, s));
         t.stop();
     }
+    // the near field first: the reduction of a face's last band adds it
+    TP_TRY(enqueue_near(B, plans, 7, true));
     for (size_t m = 0; m < B.size(); ++m) {
         if (!sym[m]) continue;
         tp_problem* P = B[m];
+        const PairPlan& pl = plans[m];
         const double pp = (double)P->nF * (double)(P->nF - 1);
-        PairTimer t(kKindGrad, pp, 0.0, s);
-        TP_HIP(launch_grad_sym(P->fd, P->symp.p, prec, P->prm.alpha, P->prm.beta, (float)P->rho2, s));
-        t.stop();
+        TP_TRY(for_each_sym_band(P->prm, P->nF, 7, [&](int K, int a0, int a1, double share) -> tp_status {
+            PairTimer t(kKindGrad, pp * share, 0.0, s);
+            TP_HIP(launch_grad_sym(P->fd, P->symp.p, K, a0, a1, prec, P->prm.alpha, P->prm.beta, (float)P->rho2, s));
+            t.stop();
+            TP_HIP(launch_reduce_sym_band(P->symp.p, P->nF, 7, K, a0, a1, near_field(P) ? P->part.p : nullptr,
+                                          P->gface.p, pl.irows, s));
+            return TP_OK;
+        }));
     }
-    TP_TRY(enqueue_near(B, plans, 7, true));
     for (size_t m = 0; m < B.size(); ++m) {
         tp_problem* P = B[m];
         const PairPlan& pl = plans[m];
         const int slices = pl.n_split + (near_field(P) ? 1 : 0);
-        if (sym[m])
-            TP_HIP(launch_reduce_sym(P->symp.p, P->nF, 7, near_field(P) ? P->part.p : nullptr, P->gface.p, pl.irows, s));
-        else
+        if (!sym[m])
             TP_HIP(launch_reduce_splits(P->part.p, slices, 7, pl.irows, P->nF, P->gface.p, pl.irows, s));
         TP_HIP(launch_grad_gather(P->V.p, P->F.p, P->nV, P->nF, P->vf_off.p, P->vf_idx.p, P->gface.p,
                                   pl.irows, dE[m], s));
@@ -1443,7 +1477,7 @@ tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, in
                 continue;
             }
             if (sym_frac_eligible(P->prm, P->nF, kc)) {
-                TP_TRY(P->symp.ensure(frac_sym_part_floats(P->nF, kc), s));
+                TP_TRY(P->symp.ensure(sym_buffer_floats(P->prm, P->nF, kc), s));
                 sym[m] = 1;
                 continue;
             }
@@ -1460,17 +1494,23 @@ tp_status enqueue_fractional(const Batch& B, const double* const* u, int ldu, in
         for (size_t m = 0; m < B.size(); ++m) {
             if (!sym[m]) continue;
             tp_problem* P = B[m];
+            const PairPlan& pl = plans[m];
             const double pp = (double)P->nF * (double)(P->nF - 1);
-            PairTimer t(kKindFrac, pp, pp * kc, s);
-            TP_HIP(launch_frac_sym(P->fd, reinterpret_cast<const float*>(P->ub.p), P->symp.p, prec, P->sigma, kc, s));
-            t.stop();
+            TP_TRY(for_each_sym_band(P->prm, P->nF, kc, [&](int K, int a0, int a1, double share) -> tp_status {
+                PairTimer t(kKindFrac, pp * share, pp * share * kc, s);
+                TP_HIP(launch_frac_sym(P->fd, reinterpret_cast<const float*>(P->ub.p), P->symp.p, K, a0, a1, prec,
+                                       P->sigma, kc, s));
+                t.stop();
+                TP_HIP(launch_reduce_sym_band(P->symp.p, P->nF, kc, K, a0, a1, nullptr, P->zbuf.p, pl.irows, s));
+                return TP_OK;
+            }));
         }
         for (size_t m = 0; m < B.size(); ++m) {
             tp_problem* P = B[m];
             const PairPlan& pl = plans[m];
-            if (sym[m])
-                TP_HIP(launch_reduce_sym(P->symp.p, P->nF, kc, nullptr, P->zbuf.p, pl.irows, s));
-            else if (!(P->prm.theta > 0.0) && !(P->prm.chi > 0.0))
+            if (sym[m]) {
+                // reduced band by band above
+            } else if (!(P->prm.theta > 0.0) && !(P->prm.chi > 0.0))
                 TP_HIP(launch_reduce_splits(P->part.p, pl.n_split, kc, pl.irows, P->nF, P->zbuf.p, pl.irows, s));
             TP_HIP(launch_ut_gather(P->F.p, P->nV, P->vf_off.p, P->vf_idx.p, P->fd, P->zbuf.p, pl.irows,
                                     kc, ldl, c0, Lu[m], s));
@@ -2862,8 +2902,8 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
     const double esz = prec == TP_PREC_FP64 ? 8 : 4;
     b += 8 * part + 8 * gface + 8.0 * kf * pf.irows + (double)cap * ((kf + 3) / 4 * 4) * esz;
     double symb = 0.0;
-    if (sym_frac_eligible(prm, nF, kf)) symb = 4.0 * (double)frac_sym_part_floats(nF, kf);
-    if (sym_grad_eligible(prm, nF)) symb = std::max(symb, 4.0 * (double)frac_sym_part_floats(nF, kGradOutputs));
+    if (sym_frac_eligible(prm, nF, kf)) symb = 4.0 * (double)sym_buffer_floats(prm, nF, kf);
+    if (sym_grad_eligible(prm, nF)) symb = std::max(symb, 4.0 * (double)sym_buffer_floats(prm, nF, kGradOutputs));
     b += symb;
     // step work arrays, per-face volumes and edge lengths, CG tables
     b += 8 * n * ncol * 4 + 8 * n * 3 * 3 + 16 * f + 4096;
@@ -2965,6 +3005,7 @@ tp_status tp_params_default(tp_params* p)
     p->leaf_size = 8;
     p->chi = 0.0;
     p->sym_pairs = -1;
+    p->sym_band = 0;
     return TP_OK;
 }
 

@@ -140,33 +140,46 @@ hipError_t launch_pairs_frac(const PairJob* jobs, int njobs, int precision, doub
                              hipStream_t s);
 PairPlan plan_for(int kind, int precision, int k, int64_t nF, int64_t cap);
 
-// Sum the n_split partials of every accumulator in split order: out[acc][i].
-// Symmetric all-pairs fractional apply (each unordered pair once, both rows; FP32 pair
-// terms): face data, face-averaged columns ub ([cap][kp] FP32, kp = kc rounded up to 4),
-// tile boxes and an FP32 partial buffer of frac_sym_part_floats(nF, kc) entries.
+// Symmetric all-pairs kernels (each unordered pair once, both rows; FP32 pair terms).  Faces
+// are cut into nB blocks of frac_sym_block_faces(); a launch takes the pairs of blocks (a, b),
+// b >= a, of a band of rows a in [a0, a1), and writes, per face and slice, kc FP32 partial
+// sums: row T's sums of pair (a, b) to partT[a - a0][c][T] ([K][kc][ldp]) and row S's to
+// partS[b][c][S - a0 blk] ([nB][kc][K blk]), K = a1 - a0 at most the band height the buffer
+// was sized for.  With a single band (K = nB) the two regions are one array [nB][kc][ldp].
+// launch_reduce_sym_band then adds the band's slices to out[c * out_stride + i] in FP64, in
+// the slice order of a single launch (rows a < block of i, then b >= block of i, then the
+// near field extra), so the result does not depend on the band height.
 struct SymFracArgs {
     const float4* fx = nullptr;
     const float4* fl = nullptr;
     const float* ub = nullptr;
     const float4* tbox = nullptr;
-    float* part = nullptr;    // [nB][kc][ldp]
+    float* part = nullptr;    // row T's sums: [K][kc][ldp]
+    float* partS = nullptr;   // row S's sums: [nB][kc][ldS]
     int64_t ldp = 0;          // nB * frac_sym_block_faces()
+    int64_t ldS = 0;          // K * frac_sym_block_faces() (ldp with a single band)
     int nB = 0;               // blocks of frac_sym_block_faces() faces holding the real faces
+    int a0 = 0, a1 = 0;       // band of rows
 };
 int frac_sym_block_faces();
-size_t frac_sym_part_floats(int64_t nF, int kc);
-// The pair kernel (kc = 1..9 columns; precision as for the row-owned kernel, not
-// TP_PREC_FP64), then the sums over the slices: out[c * out_stride + i] for i < nF.
-hipError_t launch_frac_sym(const FaceData& fd, const float* ub, float* part, int precision, double sigma, int kc,
-                           hipStream_t s);
-hipError_t launch_reduce_sym(const float* part, int64_t nF, int kc, const double* extra, double* out,
-                             int64_t out_stride, hipStream_t s);
-// Symmetric E + dE (each unordered pair once, both rows; FP32 pair terms): the seven outputs
-// per face and slice into part ([nB][7][ldp] FP32, frac_sym_part_floats(nF, 7) entries);
-// with TP_PREC_FP32_NEAR64 pairs closer than sqrt(rho2) are left to the near field.
-hipError_t launch_grad_sym(const FaceData& fd, float* part, int precision, double alpha, double beta, float rho2,
-                           hipStream_t s);
+// Band height (blocks) whose partial buffer stays within max_bytes (nB when a single band
+// fits, else at least 1), and the FP32 entries of that buffer.
+int sym_band_blocks(int64_t nF, int kc, double max_bytes);
+size_t sym_part_floats(int64_t nF, int kc, int K);
+// Unordered pairs of blocks (a, b), b >= a, with a in [a0, a1).
+int64_t sym_band_units(int64_t nF, int a0, int a1);
+// The pair kernel for rows [a0, a1) of bands of height K (kc = 1..9 columns; precision as for
+// the row-owned kernel, not TP_PREC_FP64).
+hipError_t launch_frac_sym(const FaceData& fd, const float* ub, float* part, int K, int a0, int a1, int precision,
+                           double sigma, int kc, hipStream_t s);
+hipError_t launch_reduce_sym_band(const float* part, int64_t nF, int kc, int K, int a0, int a1, const double* extra,
+                                  double* out, int64_t out_stride, hipStream_t s);
+// Symmetric E + dE: the seven outputs per face and slice (kc = 7 above); with
+// TP_PREC_FP32_NEAR64 pairs closer than sqrt(rho2) are left to the near field.
+hipError_t launch_grad_sym(const FaceData& fd, float* part, int K, int a0, int a1, int precision, double alpha,
+                           double beta, float rho2, hipStream_t s);
 
+// Sum the n_split partials of every accumulator in split order: out[acc][i].
 hipError_t launch_reduce_splits(const double* part, int n_split, int nacc, int64_t irows,
                                 int64_t n, double* out, int64_t out_stride, hipStream_t s);
 

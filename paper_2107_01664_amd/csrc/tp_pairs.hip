@@ -587,9 +587,12 @@ __global__ __launch_bounds__(kBlock) void k_frac32(PairBatch jb, float expo)
 // wave 64 at a time, one lane a step (a rotation of the whole wave), carrying their own column
 // sums.  For b > a both rows collect; the diagonal blocks (b = a) are summed row by row
 // (S-side only, S = T left out), as in k_frac32.  A wave writes its S-side sums to slice b
-// and its T-side sums to slice a of an FP32 partial buffer [nB][kc][ldp]: every face gets
-// each slice exactly once (slices >= its block from its own rows, slices < its block from
-// the waves in which it was T), and k_reduce_sym adds them in slice order in FP64.
+// and its T-side sums to slice a of FP32 partial buffers: every face gets each slice exactly
+// once (slices >= its block from its own rows, slices < its block from the waves in which it
+// was T), and k_reduce_sym_band adds them in slice order in FP64.  A launch covers the rows a
+// of one band [a0, a1); slice a of row T's sums is stored at a - a0 ([K][kc][ldp]) and row
+// S's sums for the band's faces in [nB][kc][ldS], so the buffers grow with the band height K,
+// not with nB, and the reductions of successive bands add the slices in the same order.
 
 constexpr int kSymNI = 4;                 // faces S per lane
 constexpr int kSymFaces = 64 * kSymNI;    // faces per block: one wave's faces S
@@ -608,23 +611,30 @@ struct WaveRot {
     }
 };
 
-// The pair of blocks (a, b), b >= a, of a wave's unit: the nB (nB - 1) / 2 pairs a < b
-// first, row by row, then the nB diagonal ones, which do one side only and so make a
+// Pairs of blocks (a, b), b >= a, with a in the band [a0, a1): the off-diagonal ones
+// (a < b) first, row by row, then the diagonal ones, which do one side only and so make a
 // lighter last round.
-__device__ __forceinline__ void sym_unit_blocks(int64_t unit, int nB, int& a, int& b)
+__host__ __device__ __forceinline__ int64_t sym_band_offdiag(int nB, int a0, int a1)
 {
-    const int64_t noff = (int64_t)nB * (nB - 1) / 2;
+    // sum over a in [a0, a1) of nB - 1 - a
+    return (int64_t)(a1 - a0) * (nB - 1) - ((int64_t)a1 * (a1 - 1) - (int64_t)a0 * (a0 - 1)) / 2;
+}
+
+__device__ __forceinline__ bool sym_unit_blocks(int64_t unit, int nB, int a0, int a1, int& a, int& b)
+{
+    const int64_t noff = sym_band_offdiag(nB, a0, a1);
     if (unit >= noff) {
-        a = b = (int)(unit - noff);
-        return;
+        a = b = a0 + (int)(unit - noff);
+        return a < a1;
     }
-    a = 0;
+    a = a0;
     int64_t off = 0;
     while (off + (nB - 1 - a) <= unit) {
         off += nB - 1 - a;
         ++a;
     }
     b = a + 1 + (int)(unit - off);
+    return true;
 }
 
 template <int KC, bool LO, bool DIAG>
@@ -696,7 +706,7 @@ __device__ __forceinline__ void sym_unit(const SymFracArgs& A, int a, int b, int
         // 64 rotations later every face T is back in its own lane
         if (!DIAG) {
 #pragma unroll
-            for (int c = 0; c < KC; ++c) A.part[((int64_t)a * KC + c) * A.ldp + T] = -tacc[c];
+            for (int c = 0; c < KC; ++c) A.part[((int64_t)(a - A.a0) * KC + c) * A.ldp + T] = -tacc[c];
         }
     }
 }
@@ -708,9 +718,8 @@ __global__ __launch_bounds__(kBlock) void k_frac32_sym(SymFracArgs A, float expo
     const int lane = (int)threadIdx.x & 63;
     const int64_t unit = (int64_t)blockIdx.x * (kBlock / 64) + ((int)threadIdx.x >> 6);
     const int nB = A.nB;
-    if (unit >= (int64_t)nB * (nB + 1) / 2) return;   // the whole wave leaves
     int a, b;
-    sym_unit_blocks(unit, nB, a, b);
+    if (!sym_unit_blocks(unit, nB, A.a0, A.a1, a, b)) return;   // the whole wave leaves
     float3 Sh[kSymNI], Sl[kSymNI];
     float aS[kSymNI], Su[kSymNI][KC], sacc[kSymNI][KC];
 #pragma unroll
@@ -747,9 +756,9 @@ __global__ __launch_bounds__(kBlock) void k_frac32_sym(SymFracArgs A, float expo
     }
 #pragma unroll
     for (int r = 0; r < kSymNI; ++r) {
-        const int64_t S = (int64_t)a * kSymFaces + r * 64 + lane;
+        const int64_t S = (int64_t)(a - A.a0) * kSymFaces + r * 64 + lane;   // row in the band
 #pragma unroll
-        for (int c = 0; c < KC; ++c) A.part[((int64_t)b * KC + c) * A.ldp + S] = sacc[r][c];
+        for (int c = 0; c < KC; ++c) A.partS[((int64_t)b * KC + c) * A.ldS + S] = sacc[r][c];
     }
 }
 
@@ -769,29 +778,31 @@ struct GSymArgs {
     const double4* dx = nullptr;
     const double4* dn = nullptr;
     const float4* tbox = nullptr;
-    float* part = nullptr;    // [nB][kGradOut][ldp]
+    float* part = nullptr;    // row T's sums: [K][kGradOut][ldp]
+    float* partS = nullptr;   // row S's sums: [nB][kGradOut][ldS]
     int64_t ldp = 0;
+    int64_t ldS = 0;
     int nB = 0;
+    int a0 = 0, a1 = 0;       // band of rows
     float rho2 = 0.f;
 };
 
-// The seven outputs of a face from its eleven sums (FP64, as in k_grad32), into slice sl.
-__device__ __forceinline__ void gsym_store(const GSymArgs& A, int sl, int64_t f, const float (&c)[kGradAcc],
-                                           double alpha, double beta)
+// The seven outputs of face f from its eleven sums (FP64, as in k_grad32), to dst[m * ld].
+__device__ __forceinline__ void gsym_store(const GSymArgs& A, float* dst, int64_t ld, int64_t f,
+                                           const float (&c)[kGradAcc], double alpha, double beta)
 {
     const double aF = A.dx[f].w;
     const double4 N = A.dn[f];
     double a[kGradAcc];
 #pragma unroll
     for (int m = 0; m < kGradAcc; ++m) a[m] = (double)c[m];
-    float* dst = A.part + (int64_t)sl * kGradOut * A.ldp + f;
-    dst[0 * A.ldp] = (float)(aF * (alpha * (N.x * a[0] + a[1]) - beta * a[4]));
-    dst[1 * A.ldp] = (float)(aF * (alpha * (N.y * a[0] + a[2]) - beta * a[5]));
-    dst[2 * A.ldp] = (float)(aF * (alpha * (N.z * a[0] + a[3]) - beta * a[6]));
-    dst[3 * A.ldp] = (float)(aF * alpha * a[7]);
-    dst[4 * A.ldp] = (float)(aF * alpha * a[8]);
-    dst[5 * A.ldp] = (float)(aF * alpha * a[9]);
-    dst[6 * A.ldp] = (float)a[10];
+    dst[0 * ld] = (float)(aF * (alpha * (N.x * a[0] + a[1]) - beta * a[4]));
+    dst[1 * ld] = (float)(aF * (alpha * (N.y * a[0] + a[2]) - beta * a[5]));
+    dst[2 * ld] = (float)(aF * (alpha * (N.z * a[0] + a[3]) - beta * a[6]));
+    dst[3 * ld] = (float)(aF * alpha * a[7]);
+    dst[4 * ld] = (float)(aF * alpha * a[8]);
+    dst[5 * ld] = (float)(aF * alpha * a[9]);
+    dst[6 * ld] = (float)a[10];
 }
 
 template <bool LO, bool NEAR, bool DIAG, class Pow>
@@ -891,7 +902,7 @@ __device__ __forceinline__ void gsym_unit(const GSymArgs& A, int a, int b, int l
         if (!DIAG) {
 #pragma unroll
             for (int m = 0; m < 7; ++m) ct[m] = -ct[m];
-            gsym_store(A, a, T, ct, alpha, beta);
+            gsym_store(A, A.part + (int64_t)(a - A.a0) * kGradOut * A.ldp + T, A.ldp, T, ct, alpha, beta);
         }
     }
 }
@@ -902,9 +913,8 @@ __global__ __launch_bounds__(kBlock) void k_grad32_sym(GSymArgs A, double alpha,
     const int lane = (int)threadIdx.x & 63;
     const int64_t unit = (int64_t)blockIdx.x * (kBlock / 64) + ((int)threadIdx.x >> 6);
     const int nB = A.nB;
-    if (unit >= (int64_t)nB * (nB + 1) / 2) return;   // the whole wave leaves
     int a, b;
-    sym_unit_blocks(unit, nB, a, b);
+    if (!sym_unit_blocks(unit, nB, A.a0, A.a1, a, b)) return;   // the whole wave leaves
     float3 Sh[kSymNI], Sl[kSymNI], Sn[kSymNI];
     float aS[kSymNI], c[kSymNI][kGradAcc];
 #pragma unroll
@@ -943,22 +953,50 @@ __global__ __launch_bounds__(kBlock) void k_grad32_sym(GSymArgs A, double alpha,
     else
         gsym_unit<HILO, false, false>(A, a, b, lane, pw, alpha, beta, Sh, Sl, Sn, aS, c);
 #pragma unroll
-    for (int r = 0; r < kSymNI; ++r) gsym_store(A, b, (int64_t)a * kSymFaces + r * 64 + lane, c[r], alpha, beta);
+    for (int r = 0; r < kSymNI; ++r) {
+        const int64_t row = (int64_t)(a - A.a0) * kSymFaces + r * 64 + lane;   // row in the band
+        gsym_store(A, A.partS + (int64_t)b * kGradOut * A.ldS + row, A.ldS, (int64_t)a * kSymFaces + r * 64 + lane,
+                   c[r], alpha, beta);
+    }
 }
 
-// out[c][i] = sum over the nB slices, in slice order, in FP64 (then extra[c][i], the FP64
-// near field, when given).
-__global__ void k_reduce_sym(const float* __restrict__ part, int nB, int kc, int64_t ldp, int64_t n,
-                             const double* __restrict__ extra, double* __restrict__ out, int64_t out_stride)
+// The band [a0, a1) of rows, for faces i >= a0 kSymFaces (the others get nothing from it):
+// out[c][i] (0 before the first band) plus, in FP64 and in slice order, row T's slices
+// a in [a0, min(a1, block of i)), then, for faces of the band, row S's slices b >= block of
+// i and extra[c][i] (the FP64 near field, when given).  Over all bands that is the slice
+// order a = 0 .. nB - 1 of a single launch.
+__global__ void k_reduce_sym_band(const float* __restrict__ partT, const float* __restrict__ partS, int nB, int a0,
+                                  int a1, int kc, int64_t ldp, int64_t ldS, int64_t n, const double* __restrict__ extra,
+                                  double* __restrict__ out, int64_t out_stride)
 {
+    const int64_t i0 = (int64_t)a0 * kSymFaces, m = n - i0;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n * kc) return;
-    const int c = (int)(t / n);
-    const int64_t i = t - (int64_t)c * n;
-    double s = 0.0;
-    for (int sl = 0; sl < nB; ++sl) s += (double)part[((int64_t)sl * kc + c) * ldp + i];
-    if (extra) s += extra[(int64_t)c * out_stride + i];
-    out[(int64_t)c * out_stride + i] = s;
+    if (m <= 0 || t >= m * kc) return;
+    const int c = (int)(t / m);
+    const int64_t i = i0 + (t - (int64_t)c * m);
+    const int blk = (int)(i / kSymFaces);
+    double* o = out + (int64_t)c * out_stride + i;
+    double s = a0 == 0 ? 0.0 : *o;
+    // s += p[0], p[stride], ... in that order; the loads of 16 slices are issued together
+    auto add_slices = [&s](const float* __restrict__ p, int64_t stride, int cnt) {
+        constexpr int U = 16;
+        int j = 0;
+        for (; j + U <= cnt; j += U) {
+            float v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) v[u] = p[(int64_t)(j + u) * stride];
+#pragma unroll
+            for (int u = 0; u < U; ++u) s += (double)v[u];
+        }
+        for (; j < cnt; ++j) s += (double)p[(int64_t)j * stride];
+    };
+    const int ta = min(a1, blk);
+    if (ta > a0) add_slices(partT + (int64_t)c * ldp + i, (int64_t)kc * ldp, ta - a0);
+    if (blk < a1) {
+        add_slices(partS + ((int64_t)blk * kc + c) * ldS + (i - i0), (int64_t)kc * ldS, nB - blk);
+        if (extra) s += extra[(int64_t)c * out_stride + i];
+    }
+    *o = s;
 }
 
 // ============================================================== FP64 variants
@@ -1666,10 +1704,42 @@ static hipError_t launch_frac_k(const PairJob* jobs, int njobs, int precision, d
 
 int frac_sym_block_faces() { return kSymFaces; }
 
-size_t frac_sym_part_floats(int64_t nF, int kc)
+static int64_t sym_blocks(int64_t nF) { return (nF + kSymFaces - 1) / kSymFaces; }
+
+size_t sym_part_floats(int64_t nF, int kc, int K)
 {
-    const int64_t nB = (nF + kSymFaces - 1) / kSymFaces;
-    return (size_t)nB * (size_t)kc * (size_t)(nB * kSymFaces);
+    const int64_t nB = sym_blocks(nF), ldp = nB * kSymFaces;
+    if (K >= nB) return (size_t)nB * (size_t)kc * (size_t)ldp;        // one array [nB][kc][ldp]
+    return 2 * (size_t)K * (size_t)kc * (size_t)ldp;                  // [K][kc][ldp] + [nB][kc][K blk]
+}
+
+int sym_band_blocks(int64_t nF, int kc, double max_bytes)
+{
+    const int64_t nB = std::max<int64_t>(1, sym_blocks(nF));
+    if (4.0 * (double)sym_part_floats(nF, kc, (int)nB) <= max_bytes) return (int)nB;
+    const double per = 4.0 * 2.0 * (double)kc * (double)(nB * kSymFaces);   // bytes per block of height
+    return (int)std::max<double>(1.0, std::min<double>((double)nB, std::floor(max_bytes / per)));
+}
+
+int64_t sym_band_units(int64_t nF, int a0, int a1)
+{
+    return sym_band_offdiag((int)sym_blocks(nF), a0, a1) + (a1 - a0);
+}
+
+// Pointers and leading dimensions of the two slice regions for band height K.
+static void sym_regions(float* part, int64_t nF, int kc, int K, float*& partT, float*& partS, int64_t& ldp,
+                        int64_t& ldS)
+{
+    const int64_t nB = sym_blocks(nF);
+    ldp = nB * kSymFaces;
+    partT = part;
+    if (K >= nB) {
+        partS = part;
+        ldS = ldp;
+    } else {
+        partS = part + (size_t)K * (size_t)kc * (size_t)ldp;
+        ldS = (int64_t)K * kSymFaces;
+    }
 }
 
 template <int KC>
@@ -1679,8 +1749,8 @@ static void launch_frac_sym_k(const SymFracArgs& A, bool hilo, float expo, dim3 
     else hipLaunchKernelGGL((k_frac32_sym<KC, false>), grid, dim3(kBlock), 0, s, A, expo);
 }
 
-hipError_t launch_frac_sym(const FaceData& fd, const float* ub, float* part, int precision, double sigma, int kc,
-                           hipStream_t s)
+hipError_t launch_frac_sym(const FaceData& fd, const float* ub, float* part, int K, int a0, int a1, int precision,
+                           double sigma, int kc, hipStream_t s)
 {
     if (fd.nF < 1) return hipSuccess;
     if (kc < 1 || kc > 9 || precision == TP_PREC_FP64 || !fd.tbox) return hipErrorInvalidValue;
@@ -1689,12 +1759,14 @@ hipError_t launch_frac_sym(const FaceData& fd, const float* ub, float* part, int
     A.fl = fd.fl;
     A.ub = ub;
     A.tbox = fd.tbox;
-    A.part = part;
-    A.nB = (int)((fd.nF + kSymFaces - 1) / kSymFaces);
-    A.ldp = (int64_t)A.nB * kSymFaces;
+    A.nB = (int)sym_blocks(fd.nF);
+    if (K < 1 || a0 < 0 || a1 <= a0 || a1 > A.nB || a1 - a0 > K) return hipErrorInvalidValue;
+    sym_regions(part, fd.nF, kc, K, A.part, A.partS, A.ldp, A.ldS);
+    A.a0 = a0;
+    A.a1 = a1;
     // the blocks read faces [0, ldp) of arrays of cap entries
     if (A.ldp > fd.cap) return hipErrorInvalidValue;
-    const int64_t units = (int64_t)A.nB * (A.nB + 1) / 2;
+    const int64_t units = sym_band_units(fd.nF, a0, a1);
     const int64_t blocks = (units + kBlock / 64 - 1) / (kBlock / 64);
     if (blocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks);
@@ -1714,19 +1786,24 @@ hipError_t launch_frac_sym(const FaceData& fd, const float* ub, float* part, int
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_sym(const float* part, int64_t nF, int kc, const double* extra, double* out,
-                             int64_t out_stride, hipStream_t s)
+hipError_t launch_reduce_sym_band(const float* part, int64_t nF, int kc, int K, int a0, int a1, const double* extra,
+                                  double* out, int64_t out_stride, hipStream_t s)
 {
-    const int64_t total = nF * kc;
+    const int nB = (int)sym_blocks(nF);
+    if (nF < 1 || kc < 1) return hipSuccess;
+    if (K < 1 || a0 < 0 || a1 <= a0 || a1 > nB || a1 - a0 > K) return hipErrorInvalidValue;
+    float *partT, *partS;
+    int64_t ldp, ldS;
+    sym_regions(const_cast<float*>(part), nF, kc, K, partT, partS, ldp, ldS);
+    const int64_t total = (nF - (int64_t)a0 * kSymFaces) * kc;
     if (total <= 0) return hipSuccess;
-    const int nB = (int)((nF + kSymFaces - 1) / kSymFaces);
-    hipLaunchKernelGGL(k_reduce_sym, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, part, nB, kc,
-                       (int64_t)nB * kSymFaces, nF, extra, out, out_stride);
+    hipLaunchKernelGGL(k_reduce_sym_band, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, partT, partS, nB,
+                       a0, a1, kc, ldp, ldS, nF, extra, out, out_stride);
     return hipGetLastError();
 }
 
-hipError_t launch_grad_sym(const FaceData& fd, float* part, int precision, double alpha, double beta, float rho2,
-                           hipStream_t s)
+hipError_t launch_grad_sym(const FaceData& fd, float* part, int K, int a0, int a1, int precision, double alpha,
+                           double beta, float rho2, hipStream_t s)
 {
     if (fd.nF < 1) return hipSuccess;
     if (precision == TP_PREC_FP64 || !fd.tbox) return hipErrorInvalidValue;
@@ -1737,12 +1814,14 @@ hipError_t launch_grad_sym(const FaceData& fd, float* part, int precision, doubl
     A.dx = fd.dx;
     A.dn = fd.dn;
     A.tbox = fd.tbox;
-    A.part = part;
-    A.nB = (int)((fd.nF + kSymFaces - 1) / kSymFaces);
-    A.ldp = (int64_t)A.nB * kSymFaces;
+    A.nB = (int)sym_blocks(fd.nF);
+    if (K < 1 || a0 < 0 || a1 <= a0 || a1 > A.nB || a1 - a0 > K) return hipErrorInvalidValue;
+    sym_regions(part, fd.nF, kGradOut, K, A.part, A.partS, A.ldp, A.ldS);
+    A.a0 = a0;
+    A.a1 = a1;
     A.rho2 = rho2;
     if (A.ldp > fd.cap) return hipErrorInvalidValue;
-    const int64_t units = (int64_t)A.nB * (A.nB + 1) / 2;
+    const int64_t units = sym_band_units(fd.nF, a0, a1);
     const int64_t blocks = (units + kBlock / 64 - 1) / (kBlock / 64);
     if (blocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
     const dim3 grid((unsigned)blocks), block(kBlock);

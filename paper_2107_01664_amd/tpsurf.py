@@ -57,7 +57,7 @@ class Params(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("sigma", ctypes.c_double),
                 ("precision", ctypes.c_int), ("cg_rtol", ctypes.c_double), ("cg_maxiter", ctypes.c_int),
                 ("cg_precond", ctypes.c_int), ("theta", ctypes.c_double), ("leaf_size", ctypes.c_int),
-                ("chi", ctypes.c_double), ("sym_pairs", ctypes.c_int)]
+                ("chi", ctypes.c_double), ("sym_pairs", ctypes.c_int), ("sym_band", ctypes.c_int)]
 
 
 class SolveReport(ctypes.Structure):

@@ -156,6 +156,35 @@ def test_fractional_symmetric(tp, meshes, name, k, prec):
         assert rel(Ls[:, c], Lr[:, c]) <= tol_for(prec), (c, rel(Ls[:, c], Lr[:, c]))
 
 
+@pytest.mark.parametrize("name", ["small_sphere", "geodesic9", "torus37x23", "linked_small"])
+@pytest.mark.parametrize("band", [1, 2, 3])
+def test_symmetric_bands_equal_one_launch(tp, meshes, name, band):
+    """The symmetric kernels run in bands of rows of blocks (one launch and one reduction per
+    band): every band height gives bit for bit the result of a single band, since each face's
+    slices are added in the same order; meshes of 5 to 7 blocks, ragged last blocks, two
+    components, with the FP64 near field."""
+    m = meshes[name]
+    print(f"[parity] symmetric bands {name} band={band}", flush=True)
+    V, F = dev(m.V), dev(m.F, torch.int32)
+    one = tp.default_params(sym_pairs=1)
+    banded = tp.default_params(sym_pairs=1, sym_band=band)
+    E1, g1 = tp.tp_gradient(V, F, one)
+    Eb, gb = tp.tp_gradient(V, F, banded)
+    assert Eb == E1
+    assert torch.equal(gb, g1)
+    for k in (3, 9):
+        du = dev(mg.random_columns(m.nV, k, 4))
+        L1 = tp.tp_fractional_apply(V, F, du, one)
+        Lb = tp.tp_fractional_apply(V, F, du, banded)
+        assert torch.equal(Lb, L1), k
+
+
+def test_symmetric_band_rejects_negative(tp, meshes):
+    m = meshes["small_sphere"]
+    with pytest.raises(tp.TpError):
+        tp.tp_gradient(dev(m.V), dev(m.F, torch.int32), tp.default_params(sym_band=-1))
+
+
 def test_fractional_symmetric_errors(tp, meshes):
     m = meshes["small_sphere"]
     u = dev(mg.random_columns(m.nV, 1, 1))
