@@ -206,7 +206,7 @@ def parse():
     ap.add_argument("--sweep", action="store_true",
                     help="precision and Barnes-Hut sweep (bumpy sphere, linked tori) instead of the step")
     ap.add_argument("--pairs-only", action="store_true",
-                    help="time only the all-pairs launches of the step (for counter passes)")
+                    help="time only the all-pairs launches (E + dE, L^sigma u, and E alone; for counter passes)")
     ap.add_argument("--pairs-workload", default="torus40k",
                     help="workload of --pairs-only (a name known to meshgen.workload)")
     ap.add_argument("--large-solve", action="store_true",
@@ -564,18 +564,22 @@ def main():
         for _ in range(a.warmup):
             P.gradient(out=dE)
             P.fractional_apply(u, out=Lu)
+            P.energy()
         torch.cuda.synchronize()
         tp.profile_reset()
         tp.profile_enable(True)
         for _ in range(a.steps):
             P.gradient(out=dE)
             P.fractional_apply(u, out=Lu)
+            P.energy()
         torch.cuda.synchronize()
         tp.profile_enable(False)
         g, f = tp.profile_get(tp.KIND_GRAD), tp.profile_get(tp.KIND_FRAC)
+        e = tp.profile_get(tp.KIND_ENERGY)
         print(json.dumps({"pairs_only": True, "faces": nF, "grad_launches": g["launches"],
                           "grad_avg_ms": g["ms_total"] / max(1, g["launches"]),
-                          "frac_launches": f["launches"], "frac_avg_ms": f["ms_total"] / max(1, f["launches"])}),
+                          "frac_launches": f["launches"], "frac_avg_ms": f["ms_total"] / max(1, f["launches"]),
+                          "energy_launches": e["launches"], "energy_avg_ms": e["ms_total"] / max(1, e["launches"])}),
               flush=True)
         P.close()
         return

@@ -1332,9 +1332,20 @@ tp_status enqueue_energy(const Batch& B, int slot)
     const int prec = B[0]->prm.precision;
     std::vector<PairJob> jobs;
     std::vector<PairPlan> plans;
+    std::vector<char> sym(B.size(), 0);
     double pairs = 0;
-    for (tp_problem* P : B) {
-        const PairPlan pl = plan_for(kKindEnergy, prec, 1, P->nF, P->cap);
+    for (size_t m = 0; m < B.size(); ++m) {
+        tp_problem* P = B[m];
+        PairPlan pl = plan_for(kKindEnergy, prec, 1, P->nF, P->cap);
+        if (sym_grad_eligible(P->prm, P->nF)) {
+            // symmetric kernel: part = [near field slice (irows)][pair-of-blocks partials]
+            // [a_i near_i (nF)]; the near field goes to slice 0
+            sym[m] = 1;
+            pl.n_split = 0;
+            TP_TRY(P->part.ensure((size_t)pl.irows + (size_t)sym_units(P->nF) + (size_t)P->nF, s));
+            plans.push_back(pl);
+            continue;
+        }
         const int slices = pl.n_split + (near_field(P) ? 1 : 0);
         TP_TRY(P->part.ensure((size_t)slices * pl.irows, s));
         TP_TRY(P->gface.ensure((size_t)pl.irows, s));
@@ -1343,15 +1354,34 @@ tp_status enqueue_energy(const Batch& B, int slot)
         plans.push_back(pl);
         pairs += (double)P->nF * (double)(P->nF - 1);
     }
-    {
+    if (!jobs.empty()) {
         PairTimer t(kKindEnergy, pairs, 0.0, s);
         TP_HIP(launch_pairs_energy(jobs.data(), (int)jobs.size(), prec, B[0]->prm.alpha, B[0]->prm.beta, s));
+        t.stop();
+    }
+    for (size_t m = 0; m < B.size(); ++m) {
+        if (!sym[m]) continue;
+        tp_problem* P = B[m];
+        PairTimer t(kKindEnergy, (double)P->nF * (double)(P->nF - 1), 0.0, s);
+        TP_HIP(launch_energy_sym(P->fd, P->part.p + plans[m].irows, prec, P->prm.alpha, P->prm.beta, (float)P->rho2,
+                                 s));
         t.stop();
     }
     TP_TRY(enqueue_near(B, plans, 1, false));
     for (size_t m = 0; m < B.size(); ++m) {
         tp_problem* P = B[m];
         const PairPlan& pl = plans[m];
+        if (sym[m]) {
+            // E = the partials of the pairs of blocks, then sum_i a_i near_i, in that order
+            const int64_t units = sym_units(P->nF);
+            int64_t n = units;
+            if (near_field(P)) {
+                TP_HIP(launch_area_times(P->fd, P->part.p, P->nF, P->part.p + pl.irows + units, s));
+                n += P->nF;
+            }
+            TP_HIP(launch_dot_cols(P->part.p + pl.irows, 1, nullptr, 0, n, 1, P->red.p, P->scal.p + slot, s));
+            continue;
+        }
         const int slices = pl.n_split + (near_field(P) ? 1 : 0);
         TP_HIP(launch_reduce_splits(P->part.p, slices, 1, pl.irows, P->nF, P->gface.p, pl.irows, s));
         // E = sum_S a_S sum_T a_T K(S,T)
@@ -2896,8 +2926,9 @@ uint64_t estimate_bytes(int64_t nV, int64_t nF, int max_degree, int ncomp, const
     const PairPlan pg = plan_for(kKindGrad, prec, 1, nF, cap);
     const int kf = std::min(ncol, kMaxGroupCols);
     const PairPlan pf = plan_for(kKindFrac, prec, kf, nF, cap);
-    const double part = std::max({(double)(pe.n_split + 1) * pe.irows, 7.0 * (pg.n_split + 1) * pg.irows,
-                                  (double)kf * pf.n_split * pf.irows});
+    double part = std::max({(double)(pe.n_split + 1) * pe.irows, 7.0 * (pg.n_split + 1) * pg.irows,
+                            (double)kf * pf.n_split * pf.irows});
+    if (sym_grad_eligible(prm, nF)) part = std::max(part, (double)pe.irows + (double)sym_units(nF) + (double)nF);
     const double gface = std::max((double)pe.irows, 7.0 * pg.irows);
     const double esz = prec == TP_PREC_FP64 ? 8 : 4;
     b += 8 * part + 8 * gface + 8.0 * kf * pf.irows + (double)cap * ((kf + 3) / 4 * 4) * esz;

@@ -179,6 +179,14 @@ hipError_t launch_reduce_sym_band(const float* part, int64_t nF, int kc, int K, 
 hipError_t launch_grad_sym(const FaceData& fd, float* part, int K, int a0, int a1, int precision, double alpha,
                            double beta, float rho2, hipStream_t s);
 
+// Symmetric energy (each unordered pair once; FP32 pair terms): one FP64 partial per pair of
+// blocks, sym_units(nF) of them, into upart (their sum, plus the near field's
+// sum_i a_i near[i] when pairs closer than sqrt(rho2) are left to it, is E).
+int64_t sym_units(int64_t nF);
+hipError_t launch_energy_sym(const FaceData& fd, double* upart, int precision, double alpha, double beta, float rho2,
+                             hipStream_t s);
+hipError_t launch_area_times(const FaceData& fd, const double* near, int64_t n, double* out, hipStream_t s);
+
 // Sum the n_split partials of every accumulator in split order: out[acc][i].
 hipError_t launch_reduce_splits(const double* part, int n_split, int nacc, int64_t irows,
                                 int64_t n, double* out, int64_t out_stride, hipStream_t s);

@@ -960,6 +960,156 @@ __global__ __launch_bounds__(kBlock) void k_grad32_sym(GSymArgs A, double alpha,
     }
 }
 
+// ============================================================== symmetric energy (FP32)
+//
+// The energy alone needs no per-face sums: an unordered pair (S, T) adds
+// a_S a_T (K(S,T) + K(T,S)) (a_S a_T K(S,T) on diagonal blocks, where both orders come up),
+// so only the faces S of a lane collect, the faces T pass along the wave with their
+// positions, areas and normals (7 values a step, 10 with the low parts), and each wave writes
+// one FP64 partial for its pair of blocks; the partials are summed in a fixed order.
+
+struct ESymArgs {
+    const float4* fx = nullptr;
+    const float4* fl = nullptr;
+    const float4* fn = nullptr;
+    const float4* tbox = nullptr;
+    double* upart = nullptr;   // one partial per pair of blocks
+    int64_t nF = 0;
+    int nB = 0;
+    float rho2 = 0.f;
+};
+
+template <bool LO, bool NEAR, bool DIAG, class Pow>
+__device__ __forceinline__ void esym_unit(const ESymArgs& A, int a, int b, int lane, const Pow& pw,
+                                          const float3 (&Sh)[kSymNI], const float3 (&Sl)[kSymNI],
+                                          const float3 (&Sn)[kSymNI], double (&acc)[kSymNI])
+{
+    const WaveRot rot(lane);
+    for (int q = 0; q < kSymFaces / 64; ++q) {
+        const int64_t T = (int64_t)b * kSymFaces + q * 64 + lane;
+        float4 th = A.fx[T];
+        float3 tl = make_float3(0.f, 0.f, 0.f);
+        if (LO) {
+            const float4 l = A.fl[T];
+            tl = make_float3(l.x, l.y, l.z);
+        }
+        const float4 n4 = A.fn[T];
+        float3 tn = make_float3(n4.x, n4.y, n4.z);
+        int ti = (int)T;
+        float c[kSymNI];
+#pragma unroll
+        for (int r = 0; r < kSymNI; ++r) c[r] = 0.f;
+#pragma unroll 1
+        for (int step = 0; step < 64; ++step) {
+#pragma unroll
+            for (int r = 0; r < kSymNI; ++r) {
+                float dx, dy, dz;
+                if (LO) {
+                    dx = (Sh[r].x - th.x) + (Sl[r].x - tl.x);
+                    dy = (Sh[r].y - th.y) + (Sl[r].y - tl.y);
+                    dz = (Sh[r].z - th.z) + (Sl[r].z - tl.z);
+                } else {
+                    dx = Sh[r].x - th.x;
+                    dy = Sh[r].y - th.y;
+                    dz = Sh[r].z - th.z;
+                }
+                float r2 = dist2_32(dx, dy, dz);
+                if (DIAG) r2 = ((int)((int64_t)a * kSymFaces + r * 64 + lane) == ti) ? 1.0f : r2;
+                if (NEAR) r2 = r2 < A.rho2 ? INFINITY : r2;   // summed by the FP64 near field
+                const float inv = rcp_fast(r2);
+                const float qs = Sn[r].x * dx + Sn[r].y * dy + Sn[r].z * dz;
+                float K = pw.K(qs, r2, inv);
+                if (!DIAG) {
+                    const float qt = tn.x * dx + tn.y * dy + tn.z * dz;
+                    K += pw.K(qt, r2, inv);
+                }
+                c[r] += K * th.w;
+            }
+            th.x = rot(th.x);
+            th.y = rot(th.y);
+            th.z = rot(th.z);
+            th.w = rot(th.w);
+            if (LO) {
+                tl.x = rot(tl.x);
+                tl.y = rot(tl.y);
+                tl.z = rot(tl.z);
+            }
+            if (!DIAG) {
+                tn.x = rot(tn.x);
+                tn.y = rot(tn.y);
+                tn.z = rot(tn.z);
+            }
+            if (DIAG) ti = rot(ti);
+        }
+#pragma unroll
+        for (int r = 0; r < kSymNI; ++r) acc[r] += (double)c[r];
+    }
+}
+
+template <bool HILO, bool NEAR, class Pow>
+__global__ __launch_bounds__(kBlock) void k_energy32_sym(ESymArgs A, Pow pw)
+{
+    const int lane = (int)threadIdx.x & 63;
+    const int64_t unit = (int64_t)blockIdx.x * (kBlock / 64) + ((int)threadIdx.x >> 6);
+    const int nB = A.nB;
+    int a, b;
+    if (!sym_unit_blocks(unit, nB, 0, nB, a, b)) return;   // the whole wave leaves
+    float3 Sh[kSymNI], Sl[kSymNI], Sn[kSymNI];
+    float aS[kSymNI];
+    double acc[kSymNI];
+#pragma unroll
+    for (int r = 0; r < kSymNI; ++r) {
+        const int64_t S = (int64_t)a * kSymFaces + r * 64 + lane;
+        const float4 x = A.fx[S], n = A.fn[S];
+        Sh[r] = make_float3(x.x, x.y, x.z);
+        Sn[r] = make_float3(n.x, n.y, n.z);
+        aS[r] = x.w;
+        if (HILO) {
+            const float4 l = A.fl[S];
+            Sl[r] = make_float3(l.x, l.y, l.z);
+        } else {
+            Sl[r] = make_float3(0.f, 0.f, 0.f);
+        }
+        acc[r] = 0.0;
+    }
+    bool near = false, far = HILO;
+    if (NEAR || HILO) {
+        float4 ilo, ihi;
+        irange_box(A.tbox, (int64_t)a * kSymFaces, kSymFaces, ilo, ihi);
+        for (int t = 0; t < kSymFaces / kTileJ; ++t) {
+            const int jt = b * (kSymFaces / kTileJ) + t;
+            if (NEAR) near = near || tile_may_be_near(ilo, ihi, A.tbox, jt, A.rho2);
+            if (HILO) far = far && tile_is_far(ilo, ihi, A.tbox, jt);
+        }
+    }
+    if (a == b)
+        esym_unit<HILO, NEAR, true>(A, a, b, lane, pw, Sh, Sl, Sn, acc);
+    else if (NEAR && near)
+        esym_unit<HILO, NEAR, false>(A, a, b, lane, pw, Sh, Sl, Sn, acc);
+    else if (HILO && far)
+        esym_unit<false, false, false>(A, a, b, lane, pw, Sh, Sl, Sn, acc);
+    else
+        esym_unit<HILO, false, false>(A, a, b, lane, pw, Sh, Sl, Sn, acc);
+    // the lane's faces S (padding faces, which can meet each other at distance 0, left out),
+    // then the wave's sum by an xor butterfly: every lane adds the same two values in the
+    // same order, so all lanes hold the same bits
+    double e = 0.0;
+#pragma unroll
+    for (int r = 0; r < kSymNI; ++r)
+        if ((int64_t)a * kSymFaces + r * 64 + lane < A.nF) e += (double)aS[r] * acc[r];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) e += __shfl_xor(e, m, 64);
+    if (lane == 0) A.upart[unit] = e;
+}
+
+// out[i] = a_i near[i] (the near field's share of the energy per face), i < n.
+__global__ void k_area_times(const double4* __restrict__ dx, const double* __restrict__ near, int64_t n,
+                             double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = dx[i].w * near[i];
+}
+
 // The band [a0, a1) of rows, for faces i >= a0 kSymFaces (the others get nothing from it):
 // out[c][i] (0 before the first band) plus, in FP64 and in slice order, row T's slices
 // a in [a0, min(a1, block of i)), then, for faces of the band, row S's slices b >= block of
@@ -1838,6 +1988,50 @@ hipError_t launch_grad_sym(const FaceData& fd, float* part, int K, int a0, int a
         else if (hilo) hipLaunchKernelGGL((k_grad32_sym<true, false, PowGen>), grid, block, 0, s, A, alpha, beta, pw);
         else hipLaunchKernelGGL((k_grad32_sym<false, false, PowGen>), grid, block, 0, s, A, alpha, beta, pw);
     }
+    return hipGetLastError();
+}
+
+int64_t sym_units(int64_t nF) { return sym_band_units(nF, 0, (int)sym_blocks(nF)); }
+
+hipError_t launch_energy_sym(const FaceData& fd, double* upart, int precision, double alpha, double beta, float rho2,
+                             hipStream_t s)
+{
+    if (fd.nF < 1) return hipSuccess;
+    if (precision == TP_PREC_FP64 || !fd.tbox) return hipErrorInvalidValue;
+    ESymArgs A;
+    A.fx = fd.fx;
+    A.fl = fd.fl;
+    A.fn = fd.fn;
+    A.tbox = fd.tbox;
+    A.upart = upart;
+    A.nF = fd.nF;
+    A.nB = (int)sym_blocks(fd.nF);
+    A.rho2 = rho2;
+    if ((int64_t)A.nB * kSymFaces > fd.cap) return hipErrorInvalidValue;
+    const int64_t units = sym_units(fd.nF);
+    const int64_t blocks = (units + kBlock / 64 - 1) / (kBlock / 64);
+    if (blocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)blocks), block(kBlock);
+    const bool hilo = precision == TP_PREC_FP32_HILO || precision == TP_PREC_FP32_NEAR64;
+    const bool near = precision == TP_PREC_FP32_NEAR64;
+    if (is_p6(alpha, beta)) {
+        const PowP6 pw;
+        if (near) hipLaunchKernelGGL((k_energy32_sym<true, true, PowP6>), grid, block, 0, s, A, pw);
+        else if (hilo) hipLaunchKernelGGL((k_energy32_sym<true, false, PowP6>), grid, block, 0, s, A, pw);
+        else hipLaunchKernelGGL((k_energy32_sym<false, false, PowP6>), grid, block, 0, s, A, pw);
+    } else {
+        const PowGen pw = make_gen(alpha, beta);
+        if (near) hipLaunchKernelGGL((k_energy32_sym<true, true, PowGen>), grid, block, 0, s, A, pw);
+        else if (hilo) hipLaunchKernelGGL((k_energy32_sym<true, false, PowGen>), grid, block, 0, s, A, pw);
+        else hipLaunchKernelGGL((k_energy32_sym<false, false, PowGen>), grid, block, 0, s, A, pw);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_area_times(const FaceData& fd, const double* near, int64_t n, double* out, hipStream_t s)
+{
+    if (n < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_area_times, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, fd.dx, near, n, out);
     return hipGetLastError();
 }
 

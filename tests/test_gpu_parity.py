@@ -112,6 +112,34 @@ def test_gradient_symmetric(tp, meshes, name, prec):
     assert rel(gs, gr) <= t, rel(gs, gr)
 
 
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("prec", [0, 1, 3])
+def test_energy_symmetric(tp, meshes, name, prec):
+    """The symmetric energy kernel (each unordered pair once, one FP64 partial per pair of
+    blocks) forced at small sizes: against the oracle and the row-by-row kernel, on meshes of
+    one block (20 faces), of ragged last blocks and of two components, with and without the
+    FP64 near field."""
+    m = meshes[name]
+    print(f"[parity] symmetric energy {name} precision={prec}", flush=True)
+    E0 = O.energy(m.V, m.F)
+    V, F = dev(m.V), dev(m.F, torch.int32)
+    Es = tp.tp_energy(V, F, tp.default_params(precision=prec, sym_pairs=1))
+    Er = tp.tp_energy(V, F, tp.default_params(precision=prec, sym_pairs=0))
+    t = tol_for(prec)
+    assert abs(Es - E0) <= t * E0, (Es, E0)
+    assert abs(Es - Er) <= t * E0, (Es, Er)
+
+
+@pytest.mark.parametrize("alpha,beta", [(4.0, 9.0), (8.0, 16.0)])
+def test_energy_symmetric_general_exponents(tp, meshes, alpha, beta):
+    m = meshes["geodesic9"]
+    print(f"[parity] symmetric energy alpha={alpha} beta={beta}", flush=True)
+    E0 = O.energy(m.V, m.F, alpha, beta)
+    E1 = tp.tp_energy(dev(m.V), dev(m.F, torch.int32), tp.default_params(alpha=alpha, beta=beta, precision=0,
+                                                                            sym_pairs=1))
+    assert abs(E1 - E0) <= tol_for(0) * E0
+
+
 @pytest.mark.parametrize("alpha,beta", [(4.0, 9.0), (8.0, 16.0)])
 def test_gradient_symmetric_general_exponents(tp, meshes, alpha, beta):
     m = meshes["geodesic9"]
