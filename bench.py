@@ -41,7 +41,7 @@ PEAK_HBM_GBS = 8000.0
 # the kernel's sources are the ones the passes measured.
 GRAD_TRAFFIC = {
     "sources": ["paper_2107_01664_amd/csrc/tp_pairs.hip", "paper_2107_01664_amd/csrc/tp_tiles.h",
-                "paper_2107_01664_amd/csrc/tp_internal.h"],
+                "paper_2107_01664_amd/csrc/tp_internal.h", "paper_2107_01664_amd/csrc/tp_sym.h"],
     "sha256": "f35b0a35dc9f6f4a816e846a6e0ac574b7728f6a75c05845a3f5fb731d171056",
     "fetch_bytes": int(58774.140625 * 1024) * 2,
     "write_bytes": 172543 * 1024,

@@ -1313,6 +1313,13 @@ bool sym_frac_eligible(const tp_params& prm, int64_t nF, int kc)
            sym_size_ok(prm, nF, kc);
 }
 
+// The operator A = B + B0 (direct sums at any theta): the FP32 precisions.
+bool sym_sobolev_eligible(const tp_params& prm, int64_t nF)
+{
+    if (prm.precision == TP_PREC_FP64 || prm.sym_pairs == 0 || nF < 1) return false;
+    return prm.sym_pairs == 1 || nF >= kSymMinFaces;
+}
+
 // E + dE: the FP32 precisions with FP64 per-face sums (not the FP32-accumulator studies).
 bool sym_grad_eligible(const tp_params& prm, int64_t nF)
 {
@@ -1835,10 +1842,17 @@ tp_status run_sobolev(tp_problem* P, const double* u, int ldu, int k, double* Au
         c.vf_off = P->vf_off.p;
         c.vf_idx = P->vf_idx.p;
         TP_TRY(P->ub.ensure(sobolev_face_bytes(prec, kc, P->cap), s));
-        TP_TRY(P->part.ensure((size_t)c.plan.n_split * 4 * kc * c.plan.irows, s));
         TP_TRY(P->zbuf.ensure((size_t)4 * kc * c.plan.irows, s));
+        if (sym_sobolev_eligible(P->prm, P->nF)) {
+            // symmetric pair kernel, 4 kc sums per face and slice, in bands of rows
+            c.sym_band = sym_band_height(P->prm, P->nF, 4 * kc);
+            TP_TRY(P->symp.ensure(sym_part_floats(P->nF, 4 * kc, c.sym_band), s));
+            c.symp = P->symp.p;
+        } else {
+            TP_TRY(P->part.ensure((size_t)c.plan.n_split * 4 * kc * c.plan.irows, s));
+            c.part = P->part.p;
+        }
         c.fu = P->ub.p;
-        c.part = P->part.p;
         c.z = P->zbuf.p;
         const double pairs = (double)P->nF * (double)(P->nF - 1);
         PairTimer t(kKindSobolev, pairs, pairs * kc, s);

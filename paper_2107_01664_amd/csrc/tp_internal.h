@@ -168,6 +168,8 @@ int sym_band_blocks(int64_t nF, int kc, double max_bytes);
 size_t sym_part_floats(int64_t nF, int kc, int K);
 // Unordered pairs of blocks (a, b), b >= a, with a in [a0, a1).
 int64_t sym_band_units(int64_t nF, int a0, int a1);
+// Pointers and leading dimensions of the two slice regions of a buffer for band height K.
+void sym_regions(float* part, int64_t nF, int kc, int K, float*& partT, float*& partS, int64_t& ldp, int64_t& ldS);
 // The pair kernel for rows [a0, a1) of bands of height K (kc = 1..9 columns; precision as for
 // the row-owned kernel, not TP_PREC_FP64).
 hipError_t launch_frac_sym(const FaceData& fd, const float* ub, float* part, int K, int a0, int a1, int precision,

@@ -17,6 +17,7 @@
 // to the 6th power, and q is small for near pairs on a smooth surface); tiles far from
 // the i-range (tile_is_far) use the high parts alone.
 #include "tp_internal.h"
+#include "tp_sym.h"
 #include "tp_tiles.h"
 
 #include <hipcub/hipcub.hpp>
@@ -593,49 +594,6 @@ __global__ __launch_bounds__(kBlock) void k_frac32(PairBatch jb, float expo)
 // of one band [a0, a1); slice a of row T's sums is stored at a - a0 ([K][kc][ldp]) and row
 // S's sums for the band's faces in [nB][kc][ldS], so the buffers grow with the band height K,
 // not with nB, and the reductions of successive bands add the slices in the same order.
-
-constexpr int kSymNI = 4;                 // faces S per lane
-constexpr int kSymFaces = 64 * kSymNI;    // faces per block: one wave's faces S
-
-// Value of the lane one below (lane 0 takes lane 63's): a rotation of the whole wave through
-// the LDS crossbar (ds_bpermute).  The pair loops are bound by vector-ALU issue (about one
-// wave-instruction per CU and clock, measured), and a DPP move would take one of those
-// slots per value; ds_bpermute takes none, only LDS bandwidth, which these loops leave idle.
-struct WaveRot {
-    int addr;   // byte address of the source lane
-    __device__ __forceinline__ explicit WaveRot(int lane) : addr(((lane + 63) & 63) << 2) {}
-    __device__ __forceinline__ int operator()(int v) const { return __builtin_amdgcn_ds_bpermute(addr, v); }
-    __device__ __forceinline__ float operator()(float v) const
-    {
-        return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(addr, __builtin_bit_cast(int, v)));
-    }
-};
-
-// Pairs of blocks (a, b), b >= a, with a in the band [a0, a1): the off-diagonal ones
-// (a < b) first, row by row, then the diagonal ones, which do one side only and so make a
-// lighter last round.
-__host__ __device__ __forceinline__ int64_t sym_band_offdiag(int nB, int a0, int a1)
-{
-    // sum over a in [a0, a1) of nB - 1 - a
-    return (int64_t)(a1 - a0) * (nB - 1) - ((int64_t)a1 * (a1 - 1) - (int64_t)a0 * (a0 - 1)) / 2;
-}
-
-__device__ __forceinline__ bool sym_unit_blocks(int64_t unit, int nB, int a0, int a1, int& a, int& b)
-{
-    const int64_t noff = sym_band_offdiag(nB, a0, a1);
-    if (unit >= noff) {
-        a = b = a0 + (int)(unit - noff);
-        return a < a1;
-    }
-    a = a0;
-    int64_t off = 0;
-    while (off + (nB - 1 - a) <= unit) {
-        off += nB - 1 - a;
-        ++a;
-    }
-    b = a + 1 + (int)(unit - off);
-    return true;
-}
 
 template <int KC, bool LO, bool DIAG>
 __device__ __forceinline__ void sym_unit(const SymFracArgs& A, int a, int b, int lane, float expo,
@@ -1876,9 +1834,7 @@ int64_t sym_band_units(int64_t nF, int a0, int a1)
     return sym_band_offdiag((int)sym_blocks(nF), a0, a1) + (a1 - a0);
 }
 
-// Pointers and leading dimensions of the two slice regions for band height K.
-static void sym_regions(float* part, int64_t nF, int kc, int K, float*& partT, float*& partS, int64_t& ldp,
-                        int64_t& ldS)
+void sym_regions(float* part, int64_t nF, int kc, int K, float*& partT, float*& partS, int64_t& ldp, int64_t& ldS)
 {
     const int64_t nB = sym_blocks(nF);
     ldp = nB * kSymFaces;

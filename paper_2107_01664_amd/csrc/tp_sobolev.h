@@ -25,6 +25,10 @@ struct SobolevCall {
     void* fu = nullptr;        // sobolev_face_bytes()
     double* part = nullptr;    // [n_split][4 kc][irows]
     double* z = nullptr;       // [4 kc][irows]
+    // symmetric pair kernel (FP32 precisions): its partial buffer, sym_part_floats(nF, 4 kc,
+    // sym_band) floats, and the band height in blocks; null for the row-by-row kernel
+    float* symp = nullptr;
+    int sym_band = 0;
 };
 
 // dinv[v] = 1 / (approximate diagonal of A at vertex v), FP32 hi/lo pair terms (c.plan
@@ -33,7 +37,8 @@ struct SobolevCall {
 hipError_t launch_sobolev_diag(const SobolevCall& c, double* dinv, hipStream_t s);
 
 // Columns [c0, c0 + kc) of u (row stride ldu) -> the same columns of Au (row stride ldo),
-// kc <= kSobCols.  The pair kernel alone is bracketed by (ev0, ev1) when they are non-null.
+// kc <= kSobCols.  The pair kernel alone is bracketed by (ev0, ev1) when they are non-null
+// (with the symmetric kernel in several bands: the band launches and their reductions).
 hipError_t launch_sobolev(const SobolevCall& c, const double* u, int ldu, int kc, double* Au, int ldo,
                           int c0, hipEvent_t ev0, hipEvent_t ev1, hipStream_t s);
 

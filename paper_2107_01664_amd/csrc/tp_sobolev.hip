@@ -27,6 +27,7 @@
 // The diagonal S = T contributes nothing: d = 0 there, so both differences and q vanish;
 // r2 is set to 1 on it to keep the powers finite.
 #include "tp_sobolev.h"
+#include "tp_sym.h"
 #include "tp_tiles.h"
 
 #include <algorithm>
@@ -219,6 +220,176 @@ __global__ __launch_bounds__(kBlock) void k_sob32(SobArgs A, float ms)
     for (int r = 0; r < NI; ++r)
 #pragma unroll
         for (int q = 0; q < 4 * KC; ++q) A.part[((int64_t)bs * 4 * KC + q) * A.irows + Si[r]] = acc[r][q];
+}
+
+// ------------------------------------------------------------------ symmetric FP32 pair sums
+//
+// Both kernel matrices are symmetric up to the areas: H_ST a_T and H0_ST a_T use
+// g = r2^-s and g0 = g (q_S^2 + q_T^2) / r2^2, which row T forms from the same bits (d
+// changes sign exactly in FP32, and only squares of it and of the q enter).  So each
+// unordered pair is evaluated once for both rows, as in the symmetric E + dE kernel: a wave
+// holds the kSymNI faces S of block a in each lane and passes the faces T of block b along
+// the wave with their columns and their own sums (row T's sums collect g a_S (v(S) - v(T)),
+// the negation of its terms, and are negated on the store).  Partial sums per face and
+// slice (4 kc of them) go to the banded FP32 buffers of the other symmetric kernels and are
+// reduced in slice order by launch_reduce_sym_band.
+
+struct SobSymArgs {
+    const float4* fx = nullptr;
+    const float4* fl = nullptr;
+    const float4* fn = nullptr;
+    const float4* fu = nullptr;   // [cap][KC]
+    const float4* tbox = nullptr;
+    float* part = nullptr;        // row T's sums: [K][4 KC][ldp]
+    float* partS = nullptr;       // row S's sums: [nB][4 KC][ldS]
+    int64_t ldp = 0, ldS = 0;
+    int nB = 0, a0 = 0, a1 = 0;
+};
+
+template <int KC, bool LO, bool DIAG>
+__device__ __forceinline__ void sob_sym_unit(const SobSymArgs& A, int a, int b, int lane, float ms,
+                                             const float3 (&Sh)[kSymNI], const float3 (&Sl)[kSymNI],
+                                             const float3 (&Sn)[kSymNI], const float (&aS)[kSymNI],
+                                             const float4 (&Su)[kSymNI][KC], float (&sacc)[kSymNI][4 * KC])
+{
+    const WaveRot rot(lane);
+    for (int q = 0; q < kSymFaces / 64; ++q) {
+        const int64_t T = (int64_t)b * kSymFaces + q * 64 + lane;
+        float4 th = A.fx[T];
+        float3 tl = make_float3(0.f, 0.f, 0.f);
+        if (LO) {
+            const float4 l = A.fl[T];
+            tl = make_float3(l.x, l.y, l.z);
+        }
+        const float4 n4 = A.fn[T];
+        float3 tn = make_float3(n4.x, n4.y, n4.z);
+        float4 tu[KC];
+        float tacc[4 * KC];
+#pragma unroll
+        for (int c = 0; c < KC; ++c) tu[c] = A.fu[T * KC + c];
+#pragma unroll
+        for (int m = 0; m < 4 * KC; ++m) tacc[m] = 0.f;
+        int ti = (int)T;
+#pragma unroll 1
+        for (int step = 0; step < 64; ++step) {
+#pragma unroll
+            for (int r = 0; r < kSymNI; ++r) {
+                float dx, dy, dz;
+                if (LO) {
+                    dx = (Sh[r].x - th.x) + (Sl[r].x - tl.x);
+                    dy = (Sh[r].y - th.y) + (Sl[r].y - tl.y);
+                    dz = (Sh[r].z - th.z) + (Sl[r].z - tl.z);
+                } else {
+                    dx = Sh[r].x - th.x;
+                    dy = Sh[r].y - th.y;
+                    dz = Sh[r].z - th.z;
+                }
+                float r2 = dx * dx + dy * dy + dz * dz;
+                if (DIAG) r2 = ((int)((int64_t)a * kSymFaces + r * 64 + lane) == ti) ? 1.0f : r2;
+                const float g = __builtin_amdgcn_exp2f(ms * __builtin_amdgcn_logf(r2));
+                const float qs = Sn[r].x * dx + Sn[r].y * dy + Sn[r].z * dz;
+                const float qt = tn.x * dx + tn.y * dy + tn.z * dz;
+                const float inv = __builtin_amdgcn_rcpf(r2);
+                const float g0 = g * ((qs * qs + qt * qt) * (inv * inv));
+                const float wT = g * th.w, w0T = g0 * th.w;
+                const float wS = g * aS[r], w0S = g0 * aS[r];
+#pragma unroll
+                for (int c = 0; c < KC; ++c) {
+                    const float ex = Su[r][c].x - tu[c].x, ey = Su[r][c].y - tu[c].y;
+                    const float ez = Su[r][c].z - tu[c].z, ew = Su[r][c].w - tu[c].w;
+                    sacc[r][4 * c + 0] += wT * ex;
+                    sacc[r][4 * c + 1] += wT * ey;
+                    sacc[r][4 * c + 2] += wT * ez;
+                    sacc[r][4 * c + 3] += w0T * ew;
+                    if (!DIAG) {   // minus row T's terms (negated on the store)
+                        tacc[4 * c + 0] += wS * ex;
+                        tacc[4 * c + 1] += wS * ey;
+                        tacc[4 * c + 2] += wS * ez;
+                        tacc[4 * c + 3] += w0S * ew;
+                    }
+                }
+            }
+            th.x = rot(th.x);
+            th.y = rot(th.y);
+            th.z = rot(th.z);
+            th.w = rot(th.w);
+            if (LO) {
+                tl.x = rot(tl.x);
+                tl.y = rot(tl.y);
+                tl.z = rot(tl.z);
+            }
+            tn.x = rot(tn.x);
+            tn.y = rot(tn.y);
+            tn.z = rot(tn.z);
+#pragma unroll
+            for (int c = 0; c < KC; ++c) {
+                tu[c].x = rot(tu[c].x);
+                tu[c].y = rot(tu[c].y);
+                tu[c].z = rot(tu[c].z);
+                tu[c].w = rot(tu[c].w);
+            }
+            if (!DIAG) {
+#pragma unroll
+                for (int m = 0; m < 4 * KC; ++m) tacc[m] = rot(tacc[m]);
+            }
+            if (DIAG) ti = rot(ti);
+        }
+        // 64 rotations later every face T is back in its own lane
+        if (!DIAG) {
+#pragma unroll
+            for (int m = 0; m < 4 * KC; ++m) A.part[((int64_t)(a - A.a0) * 4 * KC + m) * A.ldp + T] = -tacc[m];
+        }
+    }
+}
+
+template <int KC, bool HILO>
+__global__ __launch_bounds__(kBlock) void k_sob32_sym(SobSymArgs A, float ms)
+{
+    const int lane = (int)threadIdx.x & 63;
+    const int64_t unit = (int64_t)blockIdx.x * (kBlock / 64) + ((int)threadIdx.x >> 6);
+    int a, b;
+    if (!sym_unit_blocks(unit, A.nB, A.a0, A.a1, a, b)) return;   // the whole wave leaves
+    float3 Sh[kSymNI], Sl[kSymNI], Sn[kSymNI];
+    float aS[kSymNI], sacc[kSymNI][4 * KC];
+    float4 Su[kSymNI][KC];
+#pragma unroll
+    for (int r = 0; r < kSymNI; ++r) {
+        const int64_t S = (int64_t)a * kSymFaces + r * 64 + lane;
+        const float4 x = A.fx[S], n = A.fn[S];
+        Sh[r] = make_float3(x.x, x.y, x.z);
+        Sn[r] = make_float3(n.x, n.y, n.z);
+        aS[r] = x.w;
+        if (HILO) {
+            const float4 l = A.fl[S];
+            Sl[r] = make_float3(l.x, l.y, l.z);
+        } else {
+            Sl[r] = make_float3(0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int c = 0; c < KC; ++c) Su[r][c] = A.fu[S * KC + c];
+#pragma unroll
+        for (int m = 0; m < 4 * KC; ++m) sacc[r][m] = 0.f;
+    }
+    if (a == b) {
+        sob_sym_unit<KC, HILO, true>(A, a, b, lane, ms, Sh, Sl, Sn, aS, Su, sacc);
+    } else {
+        bool lo = HILO;
+        if (HILO) {   // blocks far apart: the high parts suffice (tile_is_far)
+            float4 ilo, ihi;
+            irange_box(A.tbox, (int64_t)a * kSymFaces, kSymFaces, ilo, ihi);
+            lo = false;
+            for (int t = 0; t < kSymFaces / kTileJ; ++t)
+                lo = lo || !tile_is_far(ilo, ihi, A.tbox, b * (kSymFaces / kTileJ) + t);
+        }
+        if (lo) sob_sym_unit<KC, HILO, false>(A, a, b, lane, ms, Sh, Sl, Sn, aS, Su, sacc);
+        else sob_sym_unit<KC, false, false>(A, a, b, lane, ms, Sh, Sl, Sn, aS, Su, sacc);
+    }
+#pragma unroll
+    for (int r = 0; r < kSymNI; ++r) {
+        const int64_t S = (int64_t)(a - A.a0) * kSymFaces + r * 64 + lane;   // row in the band
+#pragma unroll
+        for (int m = 0; m < 4 * KC; ++m) A.partS[((int64_t)b * 4 * KC + m) * A.ldS + S] = sacc[r][m];
+    }
 }
 
 // ------------------------------------------------------------------ FP64 pair sums
@@ -454,6 +625,51 @@ hipError_t launch_sobolev(const SobolevCall& c, const double* u, int ldu, int kc
     A.n_itiles = pl.n_itiles;
     A.tiles_per_split = pl.tiles_per_split;
     A.ntiles_j = pl.ntiles_j;
+    if (c.symp) {
+        if (f64 || c.sym_band < 1) return hipErrorInvalidValue;
+        const bool hilo = c.precision == TP_PREC_FP32_HILO || c.precision == TP_PREC_FP32_NEAR64;
+        SobSymArgs S;
+        S.fx = fd.fx;
+        S.fl = fd.fl;
+        S.fn = fd.fn;
+        S.fu = static_cast<const float4*>(c.fu);
+        S.tbox = fd.tbox;
+        S.nB = (int)((c.nF + kSymFaces - 1) / kSymFaces);
+        const int K = std::min(c.sym_band, S.nB);
+        sym_regions(c.symp, c.nF, 4 * kc, K, S.part, S.partS, S.ldp, S.ldS);
+        // the blocks read faces [0, ldp) of arrays of cap entries
+        if (S.ldp > fd.cap) return hipErrorInvalidValue;
+        if (ev0) (void)hipEventRecord(ev0, s);
+        for (int a0 = 0; a0 < S.nB; a0 += K) {
+            S.a0 = a0;
+            S.a1 = std::min(S.nB, a0 + K);
+            const int64_t units = sym_band_units(c.nF, S.a0, S.a1);
+            const dim3 grid((unsigned)((units + kBlock / 64 - 1) / (kBlock / 64)));
+            const float ms = (float)-c.s;
+            switch (kc) {
+            case 1:
+                if (hilo) hipLaunchKernelGGL((k_sob32_sym<1, true>), grid, dim3(kBlock), 0, s, S, ms);
+                else hipLaunchKernelGGL((k_sob32_sym<1, false>), grid, dim3(kBlock), 0, s, S, ms);
+                break;
+            case 2:
+                if (hilo) hipLaunchKernelGGL((k_sob32_sym<2, true>), grid, dim3(kBlock), 0, s, S, ms);
+                else hipLaunchKernelGGL((k_sob32_sym<2, false>), grid, dim3(kBlock), 0, s, S, ms);
+                break;
+            default:
+                if (hilo) hipLaunchKernelGGL((k_sob32_sym<3, true>), grid, dim3(kBlock), 0, s, S, ms);
+                else hipLaunchKernelGGL((k_sob32_sym<3, false>), grid, dim3(kBlock), 0, s, S, ms);
+                break;
+            }
+            if (ev1 && S.a1 == S.nB) (void)hipEventRecord(ev1, s);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            e = launch_reduce_sym_band(c.symp, c.nF, 4 * kc, K, S.a0, S.a1, nullptr, c.z, pl.irows, s);
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(k_sob_gather, dim3(nblk(c.nV * kc)), dim3(256), 0, s, c.nV, c.vf_off, c.vf_idx, c.V, c.F,
+                           fd.dx, c.z, pl.irows, kc, ldo, c0, Au);
+        return hipGetLastError();
+    }
     const dim3 grid((unsigned)(pl.n_itiles * pl.n_split));
     if (ev0) (void)hipEventRecord(ev0, s);
     switch (kc) {

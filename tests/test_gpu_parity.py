@@ -625,6 +625,36 @@ def test_sobolev_parity(tp, meshes, k, prec):
     assert max(errs) <= tol_for(prec), errs
 
 
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("k", [1, 2, 3, 4])
+@pytest.mark.parametrize("prec", [0, 1, 3])
+def test_sobolev_symmetric(tp, meshes, name, k, prec):
+    """The symmetric pair kernel of A u (each unordered pair once, for both rows) forced at
+    small sizes: against the oracle column by column and against the row-by-row kernel, on
+    meshes of one block, of ragged last blocks and of two components."""
+    m = meshes[name]
+    print(f"[parity] symmetric sobolev {name} k={k} precision={prec}", flush=True)
+    u = mg.random_columns(m.nV, k, 7)
+    A0 = O.sobolev_apply(m.V, m.F, u, S_SOB)
+    V, F, du = dev(m.V), dev(m.F, torch.int32), dev(u)
+    As = tp.tp_sobolev_apply(V, F, du, tp.default_params(precision=prec, sym_pairs=1)).cpu().numpy()
+    Ar = tp.tp_sobolev_apply(V, F, du, tp.default_params(precision=prec, sym_pairs=0)).cpu().numpy()
+    for c in range(k):
+        assert rel(As[:, c], A0[:, c]) <= tol_for(prec), (c, rel(As[:, c], A0[:, c]))
+        assert rel(As[:, c], Ar[:, c]) <= tol_for(prec), (c, rel(As[:, c], Ar[:, c]))
+
+
+@pytest.mark.parametrize("band", [1, 2])
+def test_sobolev_symmetric_bands(tp, meshes, band):
+    """Bands of rows give bit for bit the result of one band (7 blocks, ragged last block)."""
+    m = meshes["torus37x23"]
+    u = dev(mg.random_columns(m.nV, 3, 8))
+    V, F = dev(m.V), dev(m.F, torch.int32)
+    A1 = tp.tp_sobolev_apply(V, F, u, tp.default_params(sym_pairs=1))
+    Ab = tp.tp_sobolev_apply(V, F, u, tp.default_params(sym_pairs=1, sym_band=band))
+    assert torch.equal(Ab, A1)
+
+
 @pytest.mark.parametrize("name", ["small_sphere", "linked_small", "icosahedron", "geodesic9"])
 def test_sobolev_coordinates(tp, meshes, name):
     """A applied to the coordinate functions (the operator A_3 of the descent direction acts
