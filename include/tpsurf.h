@@ -109,11 +109,13 @@ typedef struct {
                             that are not separated are exact (App. B: upward pass of node
                             sums, far-field products per node, downward pass to faces);
                             see tp_problem_bct_stats                                     */
-    int    sym_pairs;     /* direct FP32 fractional apply: -1 (default) symmetric from 16,384
-                            faces on, 0 row by row (every ordered pair evaluated for its
-                            row), 1 symmetric at any size; symmetric means every unordered
-                            pair evaluated once for both rows (the kernel's g = |d|^-(2
-                            sigma + 2) is the same for both); the same choice for E + dE    */
+    int    sym_pairs;     /* direct FP32 sums of E, E + dE, the fractional apply and the
+                            operator A = B + B0: -1 (default) symmetric from 16,384 faces
+                            on, 0 row by row (every ordered pair evaluated for its row), 1
+                            symmetric at any size; symmetric means every unordered pair
+                            evaluated once for both rows (the kernel values K(S,T) and
+                            K(T,S), |d|^-(2 sigma + 2) and |d|^-2s come from the same d);
+                            E and E + dE stay row by row in precisions 4 and 5            */
     int    sym_band;      /* the symmetric kernels take the rows of 256-face blocks in bands,
                             one launch and one FP64 reduction per band, so that their FP32
                             partial buffer (2 * band * k * nF floats, or ceil(nF/256) * k *
