@@ -42,8 +42,8 @@ PEAK_HBM_GBS = 8000.0
 GRAD_TRAFFIC = {
     "sources": ["paper_2107_01664_amd/csrc/tp_pairs.hip", "paper_2107_01664_amd/csrc/tp_tiles.h",
                 "paper_2107_01664_amd/csrc/tp_internal.h", "paper_2107_01664_amd/csrc/tp_sym.h"],
-    "sha256": "f35b0a35dc9f6f4a816e846a6e0ac574b7728f6a75c05845a3f5fb731d171056",
-    "fetch_bytes": int(58774.140625 * 1024) * 2,
+    "sha256": "3e36467c93977149de4bf3719bddb0d0da665026efbf1bb3ee72bf1781d6a907",
+    "fetch_bytes": int(58736.609375 * 1024) * 2,
     "write_bytes": 172543 * 1024,
 }
 
