@@ -42,8 +42,8 @@ PEAK_HBM_GBS = 8000.0
 GRAD_TRAFFIC = {
     "sources": ["paper_2107_01664_amd/csrc/tp_pairs.hip", "paper_2107_01664_amd/csrc/tp_tiles.h",
                 "paper_2107_01664_amd/csrc/tp_internal.h", "paper_2107_01664_amd/csrc/tp_sym.h"],
-    "sha256": "3e36467c93977149de4bf3719bddb0d0da665026efbf1bb3ee72bf1781d6a907",
-    "fetch_bytes": int(58736.609375 * 1024) * 2,
+    "sha256": "5c05e40fbf4863bb757f34705e256546ea9ba153b9480c4d6d93b914f5e60f9b",
+    "fetch_bytes": int(58749.90625 * 1024) * 2,
     "write_bytes": 172543 * 1024,
 }
 

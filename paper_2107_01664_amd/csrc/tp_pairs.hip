@@ -1,6 +1,10 @@
 // All-pairs face-face kernels of the tangent-point hot path (gfx950).
 //
-// Every kernel has the same shape: a workgroup owns an i-tile of kBlock * NI faces S
+// Two shapes.  The symmetric kernels (k_grad32_sym, k_frac32_sym, k_energy32_sym, from
+// 16,384 faces on) evaluate each unordered pair once for both rows: one wave per pair of
+// 256-face blocks, faces T passed along the wave (see their section below).  The row-by-row
+// kernels (k_*32, k_*64, the FP64 near field) evaluate every ordered pair for its row: a
+// workgroup owns an i-tile of kBlock * NI faces S
 // held in registers (NI per thread) and streams a contiguous range of j-tiles of kTileJ
 // faces T through LDS; every lane reads the same T (LDS broadcast).  Each problem's
 // workgroups form an (i-tiles) x (j-splits) grid; one launch concatenates the grids of up
