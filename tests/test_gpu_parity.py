@@ -397,6 +397,28 @@ def test_bumpy327k_fp64_sampled(tp):
     assert abs((m.V * g).sum() + 2.0 * E) <= 1e-9 * np.linalg.norm(m.V) * np.linalg.norm(g)
 
 
+def test_bumpy327k_bands_bit_identical(tp):
+    """At full size the symmetric kernels run in bands of rows (45 for E + dE within the
+    512 MB partial buffer): a band height of 13 blocks instead of the default gives bit for
+    bit the same E, dE, E alone and L^sigma u (k = 3), since each face's slices are added
+    in the same order."""
+    m = mg.workload("bumpy327k")
+    print("[parity] bumpy327k symmetric kernels, two band heights", flush=True)
+    V, F = dev(m.V), dev(m.F, torch.int32)
+    u = dev(mg.random_columns(m.nV, 3, 5))
+    out = []
+    for band in (0, 13):
+        with tp.Problem(V, F, tp.default_params(sym_band=band)) as P:
+            E, g = P.gradient()
+            Ee = P.energy()
+            L = P.fractional_apply(u)
+            out.append((E, g.clone(), Ee, L.clone()))
+    (E0, g0, Ee0, L0), (E1, g1, Ee1, L1) = out
+    assert E1 == E0 and Ee1 == Ee0
+    assert torch.equal(g1, g0) and torch.equal(L1, L0)
+    assert abs(Ee0 - E0) <= TOL32 * E0   # the energy kernel against the E of E + dE
+
+
 def test_torus40k_poisson(tp, torus40k):
     m = torus40k
     b = mg.random_columns(m.nV, 3, 2)
