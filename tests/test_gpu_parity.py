@@ -666,6 +666,32 @@ def test_sobolev_symmetric(tp, meshes, name, k, prec):
         assert rel(As[:, c], Ar[:, c]) <= tol_for(prec), (c, rel(As[:, c], Ar[:, c]))
 
 
+@pytest.mark.parametrize("alpha,beta", [(4.0, 9.0), (6.0, 10.0)])
+def test_sobolev_symmetric_general_exponents(tp, meshes, alpha, beta):
+    """The symmetric kernel of A u at other exponents: the operator's order 2s follows
+    s = (beta - 2) / alpha (7/4 and 4/3 here), against the oracle with that s."""
+    m = meshes["geodesic9"]
+    s_op = (beta - 2.0) / alpha
+    print(f"[parity] symmetric sobolev alpha={alpha} beta={beta} s={s_op}", flush=True)
+    u = mg.random_columns(m.nV, 3, 9)
+    A0 = O.sobolev_apply(m.V, m.F, u, s_op)
+    A1 = tp.tp_sobolev_apply(dev(m.V), dev(m.F, torch.int32), dev(u),
+                             tp.default_params(alpha=alpha, beta=beta, precision=0, sym_pairs=1)).cpu().numpy()
+    for c in range(3):
+        assert rel(A1[:, c], A0[:, c]) <= tol_for(0), (c, rel(A1[:, c], A0[:, c]))
+
+
+def test_fractional_symmetric_sigma_override(tp, meshes):
+    """The symmetric fractional apply with sigma = 0.6 (kernel |d|^-3.2) against the oracle."""
+    m = meshes["torus37x23"]
+    u = mg.random_columns(m.nV, 3, 6)
+    L0 = O.fractional_apply(m.V, m.F, u, 0.6)
+    L1 = tp.tp_fractional_apply(dev(m.V), dev(m.F, torch.int32), dev(u),
+                                tp.default_params(sigma=0.6, sym_pairs=1)).cpu().numpy()
+    for c in range(3):
+        assert rel(L1[:, c], L0[:, c]) <= tol_for(3), (c, rel(L1[:, c], L0[:, c]))
+
+
 @pytest.mark.parametrize("band", [1, 2])
 def test_sobolev_symmetric_bands(tp, meshes, band):
     """Bands of rows give bit for bit the result of one band (7 blocks, ragged last block)."""
